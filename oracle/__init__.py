@@ -1,0 +1,252 @@
+"""Python access to the FP64 CPU oracle (``sans_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark.  The product package never imports it.
+
+``build()`` compiles ``liboracle.so`` with gcc (plain C99 + pthreads,
+``-O2 -ffp-contract=off``); ``lib()`` loads it, building it when missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "sans_oracle.c")
+SO = os.path.join(HERE, "liboracle.so")
+
+KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelepiped": 4}
+ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
+MODE = {"mc": 0, "quad": 1}
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("mode", C.c_int32),
+        ("size", C.c_double * 3), ("shell", C.c_double), ("sld", C.c_double * 3),
+        ("phi", C.c_double), ("sq_phi", C.c_double), ("sq_radius", C.c_double),
+        ("poly", C.c_double), ("poly_mask", C.c_int32), ("orient_kind", C.c_int32),
+        ("orient_mean", C.c_double * 3), ("orient_sigma", C.c_double * 3),
+        ("src_w", C.c_double), ("src_h", C.c_double), ("src_z", C.c_double),
+        ("slit_w", C.c_double), ("slit_h", C.c_double), ("slit_z", C.c_double),
+        ("lambda0", C.c_double), ("dlambda_rel", C.c_double), ("cone_alpha", C.c_double),
+        ("sample_w", C.c_double), ("sample_h", C.c_double), ("sample_d", C.c_double),
+        ("det_w", C.c_double), ("det_h", C.c_double), ("det_z", C.c_double),
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("table_size", C.c_int32), ("quad_n", C.c_int32),
+    ]
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(SO) or os.path.getmtime(SO) < os.path.getmtime(SRC):
+        tmp = SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-ffp-contract=off",
+                               "-fPIC", "-shared", "-o", tmp, SRC, "-lm", "-lpthread"])
+        os.replace(tmp, SO)
+    return SO
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(SO) or os.path.getmtime(SO) < os.path.getmtime(SRC):
+            build(force=True)
+        L = C.CDLL(SO)
+        d, u32, u64, i32 = C.c_double, C.c_uint32, C.c_uint64, C.c_int32
+        P = C.POINTER
+        L.orc_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
+        L.orc_philox_stream.argtypes = [u64, u64, u64, u32, u32, P(u32)]
+        L.orc_uniform.argtypes = [u32]
+        L.orc_uniform.restype = d
+        for f in ("orc_normal_quantile",):
+            getattr(L, f).argtypes = [d]
+            getattr(L, f).restype = d
+        for f in ("orc_schulz_quantile", "orc_gamma_p", "orc_py_g_over_x_direct"):
+            getattr(L, f).argtypes = [d, d]
+            getattr(L, f).restype = d
+        for f in ("orc_sph", "orc_lambda1", "orc_sinc"):
+            getattr(L, f).argtypes = [d]
+            getattr(L, f).restype = d
+        L.orc_py_sq.argtypes = [d, d, d]
+        L.orc_py_sq.restype = d
+        L.orc_py_series.argtypes = [d, i32, P(d)]
+        L.orc_table_normal.argtypes = [i32, P(d)]
+        L.orc_table_schulz.argtypes = [i32, d, P(d)]
+        L.orc_table_lookup.argtypes = [P(d), i32, d]
+        L.orc_table_lookup.restype = d
+        L.orc_mean_volume.argtypes = [P(OrcParams)]
+        L.orc_mean_volume.restype = d
+        L.orc_gauss_legendre.argtypes = [i32, P(d), P(d)]
+        L.orc_pq_avg.argtypes = [P(OrcParams), d, P(d)]
+        L.orc_pq_avg.restype = d
+        L.orc_amplitude.argtypes = [P(OrcParams), d, P(d), d, P(d)]
+        L.orc_amplitude.restype = d
+        L.orc_trace.argtypes = [P(OrcParams), u64, u64, u64, u32, i32, P(d), P(d), P(u64)]
+        L.orc_trace.restype = i32
+        L.orc_trace_debug.argtypes = [P(OrcParams), u64, u64, u64, u32, P(i32), P(d), P(d)]
+        L.orc_trace_debug.restype = i32
+        _LIB = L
+    return _LIB
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def to_params(p: dict) -> OrcParams:
+    """Workload parameter dict -> the oracle's own parameter struct."""
+    o = OrcParams()
+    o.kind = KIND[p["kind"]]
+    o.mode = MODE[p["mode"]]
+    for k in range(3):
+        o.size[k] = p["size"][k]
+        o.sld[k] = p["sld"][k]
+        o.orient_mean[k] = p["orient_mean"][k]
+        o.orient_sigma[k] = p["orient_sigma"][k]
+    for f in ("shell", "phi", "sq_phi", "sq_radius", "poly", "src_w", "src_h", "src_z",
+              "slit_w", "slit_h", "slit_z", "lambda0", "dlambda_rel", "cone_alpha",
+              "sample_w", "sample_h", "sample_d", "det_w", "det_h", "det_z"):
+        setattr(o, f, float(p[f]))
+    o.poly_mask = int(p["poly_mask"])
+    o.orient_kind = ORIENT[p["orient_kind"]]
+    o.nx, o.ny = int(p["nx"]), int(p["ny"])
+    o.table_size = int(p["table_size"])
+    o.quad_n = int(p["quad_n"])
+    return o
+
+
+# ---------------------------------------------------------------- wrappers
+
+def philox(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(out, C.c_uint32))
+    return out
+
+
+def philox_stream(seed: int, first: int, n: int, nblocks: int, exp_id: int = 0) -> np.ndarray:
+    out = np.zeros((n, nblocks, 4), dtype=np.uint32)
+    lib().orc_philox_stream(seed, first, n, nblocks, exp_id, _ptr(out, C.c_uint32))
+    return out
+
+
+def uniform(x: int) -> float:
+    return lib().orc_uniform(x)
+
+
+def normal_quantile(u: float) -> float:
+    return lib().orc_normal_quantile(u)
+
+
+def schulz_quantile(u: float, p: float) -> float:
+    return lib().orc_schulz_quantile(u, p)
+
+
+def gamma_p(a: float, x: float) -> float:
+    return lib().orc_gamma_p(a, x)
+
+
+def table_normal(M: int) -> np.ndarray:
+    out = np.zeros(M)
+    lib().orc_table_normal(M, _ptr(out, C.c_double))
+    return out
+
+
+def table_schulz(M: int, p: float) -> np.ndarray:
+    out = np.zeros(M)
+    lib().orc_table_schulz(M, p, _ptr(out, C.c_double))
+    return out
+
+
+def table_lookup(knots: np.ndarray, u: float) -> float:
+    k = np.ascontiguousarray(knots, dtype=np.float64)
+    return lib().orc_table_lookup(_ptr(k, C.c_double), len(k), u)
+
+
+def sph(x: float) -> float:
+    return lib().orc_sph(x)
+
+
+def lambda1(x: float) -> float:
+    return lib().orc_lambda1(x)
+
+
+def sinc(x: float) -> float:
+    return lib().orc_sinc(x)
+
+
+def py_sq(q: float, radius: float, phi: float) -> float:
+    return lib().orc_py_sq(q, radius, phi)
+
+
+def py_series(phi: float, nterms: int) -> np.ndarray:
+    out = np.zeros(nterms)
+    lib().orc_py_series(phi, nterms, _ptr(out, C.c_double))
+    return out
+
+
+def py_g_over_x_direct(x: float, phi: float) -> float:
+    return lib().orc_py_g_over_x_direct(x, phi)
+
+
+def gauss_legendre(n: int):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    lib().orc_gauss_legendre(n, _ptr(x, C.c_double), _ptr(w, C.c_double))
+    return x, w
+
+
+def mean_volume(p: dict) -> float:
+    o = to_params(p)
+    return lib().orc_mean_volume(C.byref(o))
+
+
+def pq_avg(p: dict, q: float, qvec=(0.0, 0.0, 0.0)) -> float:
+    o = to_params(p)
+    qv = np.asarray(qvec, dtype=np.float64).copy()
+    return lib().orc_pq_avg(C.byref(o), q, _ptr(qv, C.c_double))
+
+
+def amplitude(p: dict, q: float, qvec, y: float = 1.0, angles=None) -> float:
+    o = to_params(p)
+    qv = np.asarray(qvec, dtype=np.float64).copy()
+    ang = np.asarray(p["orient_mean"] if angles is None else angles, dtype=np.float64).copy()
+    return lib().orc_amplitude(C.byref(o), q, _ptr(qv, C.c_double), y, _ptr(ang, C.c_double))
+
+
+def trace(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0, nthreads: int = 1,
+          with_w2: bool = False, with_count: bool = False):
+    """Detector (ny, nx) FP64 of neutrons first..first+n-1; optionally the
+    sum of w^2 and the hit counts."""
+    o = to_params(p)
+    det = np.zeros((p["ny"], p["nx"]))
+    w2 = np.zeros_like(det) if with_w2 else None
+    cnt = np.zeros(det.shape, dtype=np.uint64) if with_count else None
+    rc = lib().orc_trace(C.byref(o), first, n, seed, exp_id, nthreads, _ptr(det, C.c_double),
+                         _ptr(w2, C.c_double) if w2 is not None else None,
+                         _ptr(cnt, C.c_uint64) if cnt is not None else None)
+    if rc != 0:
+        raise ValueError(f"oracle trace failed ({rc})")
+    if with_w2 or with_count:
+        return det, w2, cnt
+    return det
+
+
+def trace_debug(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0):
+    """Per-neutron (pixel, w, q): pixel -1 and w 0 when nothing is tallied."""
+    o = to_params(p)
+    pix = np.zeros(n, dtype=np.int32)
+    w = np.zeros(n)
+    q = np.zeros(n)
+    rc = lib().orc_trace_debug(C.byref(o), first, n, seed, exp_id, _ptr(pix, C.c_int32),
+                               _ptr(w, C.c_double), _ptr(q, C.c_double))
+    if rc != 0:
+        raise ValueError(f"oracle trace failed ({rc})")
+    return pix, w, q

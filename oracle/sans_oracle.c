@@ -1,0 +1,813 @@
+/*
+ * sans_oracle.c -- plain FP64 CPU oracle of the SANS sample tracer.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is loaded by the test-suite, by the
+ * smoke check and by the CPU-baseline leg of the benchmark, nowhere else.  The
+ * product (the HIP library) never links, loads or calls it, and the two share
+ * no code, header, table or constant generator: everything here is written
+ * out again from the paper and from textbook definitions.
+ *
+ * What it computes (arXiv 2501.06054, "Small Angle Neutron Scattering in
+ * McStas: optimization for high throughput virtual experiments"):
+ *   - each neutron is independent and scatters at most once inside the sample
+ *     (Introduction; Methods, "Acceleration schemes": the problem is
+ *     embarrassingly parallel and split scatter-gather over workers);
+ *   - the per-event intensity is I = n (drho)^2 V^2 P(Q) S(Q), Eq. (3), built
+ *     from the scattering amplitude A(Q) of Eq. (1) with |A|^2 as in Eqs. (2)
+ *     and (4); the amplitude depends on |Q| (Eq. (5)), on (Q_A, Q_B, Q_C)
+ *     (Eq. (6)) or on (Q_AB, Q_C) (Eq. (7)); cylinder amplitude Eq. (9);
+ *   - size and orientation are redrawn at every scattering event from the
+ *     configured distributions (Methods, "Polydispersity and orientational
+ *     distributions");
+ *   - detector tallies are summed in FP64 (atomic, thread-locked updates in
+ *     the paper's GPU scheme; here: one private detector per thread merged in
+ *     a fixed order, the paper's scatter-gather).
+ * Where the paper is silent (instrument, weight, random generator, tables,
+ * Schulz distribution, hard-sphere S(Q)) the readings are the ones recorded in
+ * the design notes of the repository; each function says which one it takes.
+ *
+ * Precision: FP64 throughout, compiled with -ffp-contract=off.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_MAX_QUAD 512
+
+/* ------------------------------------------------------------------------ */
+/* Parameters.  Own layout (not the product's).  Geometry in metres, sample
+ * in Angstrom; angles in radians.                                          */
+typedef struct {
+    int32_t kind;          /* 0 sphere, 1 core-shell sphere, 2 cylinder,
+                              3 triaxial ellipsoid, 4 parallelepiped        */
+    int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
+    double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C */
+    double shell;          /* core-shell shell thickness                     */
+    double sld[3];         /* particle (core), shell, solvent                */
+    double phi;            /* particle volume fraction, n = phi/<V>          */
+    double sq_phi;         /* hard-sphere volume fraction; 0 -> S = 1        */
+    double sq_radius;      /* hard-sphere radius                             */
+    double poly;           /* Schulz relative width sigma/mean; 0 -> none    */
+    int32_t poly_mask;     /* bit k: size[k] is scaled by the size draw      */
+    int32_t orient_kind;   /* 0 fixed, 1 gaussian, 2 isotropic, 3 uniform angles */
+    double orient_mean[3]; /* theta, phi, Psi                                */
+    double orient_sigma[3];
+    double src_w, src_h, src_z;
+    double slit_w, slit_h, slit_z;
+    double lambda0, dlambda_rel, cone_alpha;
+    double sample_w, sample_h, sample_d;
+    double det_w, det_h, det_z;
+    int32_t nx, ny;
+    int32_t table_size;    /* inverse-CDF knots (M)                          */
+    int32_t quad_n;        /* Gauss-Legendre order of the exact average      */
+} orc_params;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC'11): ten rounds of the 4x32 Philox S-box; the two key
+ * words are advanced by the Weyl constants before every round but the first. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* The random block b of neutron i in experiment e: counter (lo i, hi i, b, e),
+ * key (lo seed, hi seed). */
+static void neutron_block(uint64_t seed, uint64_t i, uint32_t b, uint32_t e, uint32_t out[4])
+{
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), b, e};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* Raw streams for tests: out[(j*nblocks + b)*4 + w] for neutron first+j. */
+void orc_philox_stream(uint64_t seed, uint64_t first, uint64_t n, uint32_t nblocks,
+                       uint32_t exp_id, uint32_t* out)
+{
+    for (uint64_t j = 0; j < n; ++j)
+        for (uint32_t b = 0; b < nblocks; ++b)
+            neutron_block(seed, first + j, b, exp_id, out + (j * nblocks + b) * 4);
+}
+
+/* u = (x + 1/2) 2^-32, an exact FP64 value strictly inside (0, 1). */
+double orc_uniform(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
+
+/* ------------------------------------------------------------------------ */
+/* Inverse cumulative distributions. */
+
+/* Standard normal CDF from the complementary error function. */
+static double normal_cdf(double y) { return 0.5 * erfc(-y / sqrt(2.0)); }
+
+/* Standard normal quantile: bisection of normal_cdf(y) = u (slow, plain). */
+double orc_normal_quantile(double u)
+{
+    double lo = -40.0, hi = 40.0;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (normal_cdf(mid) < u) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Regularised lower incomplete gamma P(a, x).  Series (Abramowitz & Stegun
+ * 6.5.29) below x = a + 1, otherwise 1 - Q with Q from Legendre's continued
+ * fraction (A&S 6.5.31) evaluated by the modified Lentz method. */
+double orc_gamma_p(double a, double x)
+{
+    if (x <= 0.0) return 0.0;
+    double lpre = a * log(x) - x - lgamma(a);
+    if (x < a + 1.0) {
+        double term = 1.0 / a, sum = term;
+        for (int n = 1; n < 1000000; ++n) {
+            term *= x / (a + n);
+            sum += term;
+            if (fabs(term) < fabs(sum) * 1e-17) break;
+        }
+        return sum * exp(lpre);
+    }
+    const double tiny = 1e-300;
+    double b = x + 1.0 - a;
+    double c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int n = 1; n < 1000000; ++n) {
+        double an = -n * (n - a);
+        b += 2.0;
+        d = an * d + b;
+        if (fabs(d) < tiny) d = tiny;
+        c = b + an / c;
+        if (fabs(c) < tiny) c = tiny;
+        d = 1.0 / d;
+        double del = d * c;
+        h *= del;
+        if (fabs(del - 1.0) < 1e-16) break;
+    }
+    return 1.0 - exp(lpre) * h;
+}
+
+/* Schulz distribution of the relative size y (mean 1, relative width p):
+ * y ~ Gamma(shape a = 1/p^2, scale 1/a), i.e. z = 1/p^2 - 1 in the usual
+ * Schulz notation.  Quantile by bisection of P(a, a*y) = u. */
+double orc_schulz_quantile(double u, double p)
+{
+    double a = 1.0 / (p * p);
+    double lo = 0.0, hi = 1.0;
+    while (orc_gamma_p(a, a * hi) < u) hi *= 2.0;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (orc_gamma_p(a, a * mid) < u) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Inverse-CDF table: knots y_k = F^-1((k + 1/2)/M), k = 0 .. M-1. */
+void orc_table_normal(int32_t M, double* knots)
+{
+    for (int k = 0; k < M; ++k) knots[k] = orc_normal_quantile((k + 0.5) / M);
+}
+
+void orc_table_schulz(int32_t M, double p, double* knots)
+{
+    for (int k = 0; k < M; ++k) knots[k] = orc_schulz_quantile((k + 0.5) / M, p);
+}
+
+/* Table lookup: s = u M - 1/2, k = clamp(floor(s), 0, M-2), linear
+ * interpolation between knots k and k+1 (linear extrapolation in the two end
+ * half-cells). */
+double orc_table_lookup(const double* knots, int32_t M, double u)
+{
+    double s = u * M - 0.5;
+    double fk = floor(s);
+    if (fk < 0.0) fk = 0.0;
+    if (fk > M - 2) fk = M - 2;
+    int k = (int)fk;
+    double f = s - fk;
+    return knots[k] + f * (knots[k + 1] - knots[k]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Shape functions. */
+
+/* 3 j1(x)/x = 3 (sin x - x cos x)/x^3, the normalised sphere amplitude
+ * (-> 1 as x -> 0).  Below x = 0.1 its Taylor series
+ * sum_m (-1)^m 6 (m+1) x^(2m) / (2m+3)! is summed instead. */
+double orc_sph(double x)
+{
+    x = fabs(x);
+    if (x < 0.1) {
+        double s = 0.0, x2 = x * x, xp = 1.0, fact = 6.0; /* (2m+3)! at m=0 */
+        for (int m = 0; m < 8; ++m) {
+            double term = 6.0 * (m + 1) * xp / fact;
+            s += (m % 2 == 0) ? term : -term;
+            xp *= x2;
+            fact *= (2.0 * m + 4.0) * (2.0 * m + 5.0);
+        }
+        return s;
+    }
+    return 3.0 * (sin(x) - x * cos(x)) / (x * x * x);
+}
+
+/* Lambda1(x) = 2 J1(x)/x (-> 1 as x -> 0), J1 from the C library; below
+ * 1e-3 the series 1 - x^2/8 + x^4/192. */
+double orc_lambda1(double x)
+{
+    x = fabs(x);
+    if (x < 1e-3) {
+        double x2 = x * x;
+        return 1.0 - x2 / 8.0 + x2 * x2 / 192.0;
+    }
+    return 2.0 * j1(x) / x;
+}
+
+/* sinc(x) = sin(x)/x. */
+double orc_sinc(double x)
+{
+    if (fabs(x) < 1e-4) return 1.0 - x * x / 6.0;
+    return sin(x) / x;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hard-sphere structure factor in the Percus-Yevick closure (Wertheim 1963;
+ * Kinning & Thomas 1984), the "hard sphere" model of the isotropic table:
+ *   x = 2 q R,  S = 1 / (1 + 24 phi G(x)/x),
+ *   G(x) = alpha (sin x - x cos x)/x^2
+ *        + beta (2x sin x + (2 - x^2) cos x - 2)/x^3
+ *        + gamma (-x^4 cos x + 4[(3x^2 - 6) cos x + (x^3 - 6x) sin x + 6])/x^5,
+ *   alpha = (1+2phi)^2/(1-phi)^4, beta = -6 phi (1+phi/2)^2/(1-phi)^4,
+ *   gamma = phi alpha / 2.
+ * The closed form cancels catastrophically at small x, so below x = 1 the
+ * Taylor series of G(x)/x is used; its coefficients are the x^(2m) terms of
+ * the three brackets expanded with the power series of sin and cos.        */
+static double fact(int n)
+{
+    double f = 1.0;
+    for (int k = 2; k <= n; ++k) f *= k;
+    return f;
+}
+static double sgn(int n) { return (n % 2 == 0) ? 1.0 : -1.0; }
+
+/* c[m] = coefficient of x^(2m) in G(x)/x, m = 0 .. nterms-1. */
+void orc_py_series(double phi, int32_t nterms, double* c)
+{
+    double om = 1.0 - phi;
+    double om4 = om * om * om * om;
+    double alpha = (1.0 + 2.0 * phi) * (1.0 + 2.0 * phi) / om4;
+    double beta = -6.0 * phi * (1.0 + 0.5 * phi) * (1.0 + 0.5 * phi) / om4;
+    double gamma = 0.5 * phi * alpha;
+    for (int m = 0; m < nterms; ++m) {
+        /* (sin x - x cos x)/x^3: x^(2m) coefficient */
+        double am = sgn(m) * 2.0 * (m + 1) / fact(2 * m + 3);
+        /* (2x sin x + (2 - x^2) cos x - 2)/x^4: x^(2M) of the numerator, M = m+2 */
+        int M = m + 2;
+        double bm = 2.0 * sgn(M - 1) / fact(2 * M - 1) + 2.0 * sgn(M) / fact(2 * M)
+                  - sgn(M - 1) / fact(2 * M - 2);
+        /* gamma bracket / x^6: x^(2K) of the numerator, K = m+3 */
+        int K = m + 3;
+        double gm = -sgn(K - 2) / fact(2 * K - 4) + 12.0 * sgn(K - 1) / fact(2 * K - 2)
+                  - 24.0 * sgn(K) / fact(2 * K) + 4.0 * sgn(K - 2) / fact(2 * K - 3)
+                  - 24.0 * sgn(K - 1) / fact(2 * K - 1);
+        c[m] = alpha * am + beta * bm + gamma * gm;
+    }
+}
+
+/* G(x)/x by the closed form (valid, but inaccurate for small x). */
+double orc_py_g_over_x_direct(double x, double phi)
+{
+    double om = 1.0 - phi;
+    double om4 = om * om * om * om;
+    double alpha = (1.0 + 2.0 * phi) * (1.0 + 2.0 * phi) / om4;
+    double beta = -6.0 * phi * (1.0 + 0.5 * phi) * (1.0 + 0.5 * phi) / om4;
+    double gamma = 0.5 * phi * alpha;
+    double s = sin(x), c = cos(x);
+    double x2 = x * x, x3 = x2 * x, x4 = x2 * x2, x5 = x4 * x;
+    double G = alpha * (s - x * c) / x2
+             + beta * (2.0 * x * s + (2.0 - x2) * c - 2.0) / x3
+             + gamma * (-x4 * c + 4.0 * ((3.0 * x2 - 6.0) * c + (x3 - 6.0 * x) * s + 6.0)) / x5;
+    return G / x;
+}
+
+double orc_py_sq(double q, double radius, double phi)
+{
+    if (phi <= 0.0) return 1.0;
+    double x = 2.0 * q * radius;
+    double gx;
+    if (x < 1.0) {
+        double c[14];
+        orc_py_series(phi, 14, c);
+        double x2 = x * x, xp = 1.0;
+        gx = 0.0;
+        for (int m = 0; m < 14; ++m) { gx += c[m] * xp; xp *= x2; }
+    } else {
+        gx = orc_py_g_over_x_direct(x, phi);
+    }
+    return 1.0 / (1.0 + 24.0 * phi * gx);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Particle amplitudes F (the Fourier transform of the excess scattering
+ * length density, Eq. (1)), in Angstrom: F^2 = (drho V)^2 P.  The particle
+ * axes A, B, C are given in the laboratory frame; Q_A = Q.A etc.           */
+
+static double vol_sphere(double r) { return 4.0 / 3.0 * ORC_PI * r * r * r; }
+
+/* Amplitude for one set of (possibly scaled) sizes. */
+static double amplitude(int kind, const double s[3], double shell, const double sld[3],
+                        double q, double qa, double qb, double qc)
+{
+    double drho = sld[0] - sld[2];
+    switch (kind) {
+    case 0: /* sphere, isotropic, Eq. (5) */
+        return drho * vol_sphere(s[0]) * orc_sph(q * s[0]);
+    case 1: { /* core-shell sphere: core minus shell contrast plus shell minus solvent */
+        double rc = s[0], ro = s[0] + shell;
+        return (sld[0] - sld[1]) * vol_sphere(rc) * orc_sph(q * rc)
+             + (sld[1] - sld[2]) * vol_sphere(ro) * orc_sph(q * ro);
+    }
+    case 2: { /* cylinder, one symmetry axis C, Eqs. (7) and (9): the sinc factor
+                 takes the projection on the axis and half the length, the
+                 Bessel factor the projection on the AB plane and the radius */
+        double r = s[0], len = s[1];
+        double qab2 = q * q - qc * qc;
+        double qab = qab2 > 0.0 ? sqrt(qab2) : 0.0;
+        return drho * ORC_PI * r * r * len * orc_sinc(0.5 * qc * len) * orc_lambda1(qab * r);
+    }
+    case 3: { /* triaxial ellipsoid, semi-axes a, b, c along A, B, C, Eq. (6) */
+        double a = s[0], b = s[1], c = s[2];
+        double x = sqrt((a * qa) * (a * qa) + (b * qb) * (b * qb) + (c * qc) * (c * qc));
+        return drho * 4.0 / 3.0 * ORC_PI * a * b * c * orc_sph(x);
+    }
+    case 4: { /* parallelepiped, edges A, B, C, Eq. (6) */
+        double a = s[0], b = s[1], c = s[2];
+        return drho * a * b * c * orc_sinc(0.5 * qa * a) * orc_sinc(0.5 * qb * b)
+             * orc_sinc(0.5 * qc * c);
+    }
+    }
+    return 0.0;
+}
+
+/* Sizes scaled by the relative size draw y according to the mask. */
+static void scaled_sizes(const orc_params* p, double y, double s[3])
+{
+    for (int k = 0; k < 3; ++k) s[k] = (p->poly_mask >> k & 1) ? p->size[k] * y : p->size[k];
+}
+
+/* Schulz moments <y^k> = prod_{j=0}^{k-1} (a + j)/a with a = 1/p^2. */
+static double schulz_moment(double p, int k)
+{
+    if (p <= 0.0) return 1.0;
+    double a = 1.0 / (p * p), m = 1.0;
+    for (int j = 0; j < k; ++j) m *= (a + j) / a;
+    return m;
+}
+
+/* Number-averaged particle volume <V> (n = phi/<V>). */
+double orc_mean_volume(const orc_params* p)
+{
+    double pr = p->poly;
+    const double* s = p->size;
+    int b0 = p->poly_mask & 1, b1 = p->poly_mask >> 1 & 1, b2 = p->poly_mask >> 2 & 1;
+    switch (p->kind) {
+    case 0:
+        return vol_sphere(s[0]) * schulz_moment(pr, b0 ? 3 : 0);
+    case 1: {
+        double r = s[0], t = p->shell;
+        if (!b0) return vol_sphere(r + t);
+        return 4.0 / 3.0 * ORC_PI * (r * r * r * schulz_moment(pr, 3)
+                                      + 3.0 * r * r * t * schulz_moment(pr, 2)
+                                      + 3.0 * r * t * t * schulz_moment(pr, 1) + t * t * t);
+    }
+    case 2:
+        return ORC_PI * s[0] * s[0] * s[1] * schulz_moment(pr, 2 * b0 + b1);
+    case 3:
+        return 4.0 / 3.0 * ORC_PI * s[0] * s[1] * s[2] * schulz_moment(pr, b0 + b1 + b2);
+    case 4:
+        return s[0] * s[1] * s[2] * schulz_moment(pr, b0 + b1 + b2);
+    }
+    return 0.0;
+}
+
+/* Particle axes from the angles (theta, phi, Psi): R = Rz(phi) Ry(theta)
+ * Rz(Psi); C = R z (theta, phi give the C axis), A = R x, B = R y (Psi turns
+ * A, B about C), as the orientation angles are defined with Eq. (6).       */
+static void particle_axes(const double ang[3], double A[3], double B[3], double C[3])
+{
+    double ct = cos(ang[0]), st = sin(ang[0]);
+    double cp = cos(ang[1]), sp = sin(ang[1]);
+    double cs = cos(ang[2]), ss = sin(ang[2]);
+    A[0] = cp * ct * cs - sp * ss;
+    A[1] = sp * ct * cs + cp * ss;
+    A[2] = -st * cs;
+    B[0] = -cp * ct * ss - sp * cs;
+    B[1] = -sp * ct * ss + cp * cs;
+    B[2] = st * ss;
+    C[0] = cp * st;
+    C[1] = sp * st;
+    C[2] = ct;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gauss-Legendre nodes and weights on [-1, 1]: Newton iteration on P_n with
+ * the three-term recurrence (n P_n = (2n-1) x P_{n-1} - (n-1) P_{n-2}).     */
+void orc_gauss_legendre(int32_t n, double* x, double* w)
+{
+    for (int i = 0; i < n; ++i) {
+        double z = cos(ORC_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        /* recompute the derivative at the converged node */
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = -z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+/* Schulz probability density of y (mean 1, relative width p). */
+static double schulz_pdf(double y, double p)
+{
+    double a = 1.0 / (p * p);
+    if (y <= 0.0) return 0.0;
+    return exp(a * log(a) + (a - 1.0) * log(y) - a * y - lgamma(a));
+}
+
+/* Exact average <F^2>(q) that replaces the per-event size and orientation
+ * draws in quadrature mode: Schulz size average by quad_n Gauss-Legendre
+ * nodes on y in [max(0, 1-6p), 1+8p] (weights normalised to the quadrature
+ * of the density) and, for isotropic orientation, the orientation average
+ *   <g> = int_0^1 dmu g(mu)                     (one symmetry axis, Eq. (7))
+ *   <g> = (2/pi) int_0^1 dmu int_0^(pi/2) dbeta g(mu, beta)   (Eq. (6))
+ * with Q_C = q mu, Q_A = q sqrt(1-mu^2) cos beta, Q_B = q sqrt(1-mu^2) sin beta.
+ * Fixed orientation evaluates the amplitude at the given Q vector.          */
+static double pq_avg_nodes(const orc_params* p, double q, const double qvec[3],
+                           const double* gx, const double* gw)
+{
+    int n = p->quad_n;
+
+    /* size nodes */
+    int ny = 1;
+    double ys[ORC_MAX_QUAD], yw[ORC_MAX_QUAD];
+    ys[0] = 1.0;
+    yw[0] = 1.0;
+    if (p->poly > 0.0) {
+        double lo = 1.0 - 6.0 * p->poly, hi = 1.0 + 8.0 * p->poly;
+        if (lo < 0.0) lo = 0.0;
+        double norm = 0.0;
+        ny = n;
+        for (int j = 0; j < n; ++j) {
+            ys[j] = 0.5 * (hi - lo) * gx[j] + 0.5 * (hi + lo);
+            yw[j] = 0.5 * (hi - lo) * gw[j] * schulz_pdf(ys[j], p->poly);
+            norm += yw[j];
+        }
+        for (int j = 0; j < n; ++j) yw[j] /= norm;
+    }
+
+    int aniso = (p->kind >= 2);
+    int iso = aniso && p->orient_kind == 2;
+    /* a spheroid (a = b, scaled alike) needs only the angle to its C axis */
+    int one_axis = (p->kind == 2)
+                || (p->kind == 3 && p->size[0] == p->size[1]
+                    && (p->poly_mask & 1) == (p->poly_mask >> 1 & 1));
+    double A[3], B[3], C[3];
+    particle_axes(p->orient_mean, A, B, C);
+
+    double total = 0.0;
+    for (int j = 0; j < ny; ++j) {
+        double s[3];
+        scaled_sizes(p, ys[j], s);
+        double avg = 0.0;
+        if (!aniso) {
+            double f = amplitude(p->kind, s, p->shell, p->sld, q, 0.0, 0.0, 0.0);
+            avg = f * f;
+        } else if (!iso) {
+            double qa = qvec[0] * A[0] + qvec[1] * A[1] + qvec[2] * A[2];
+            double qb = qvec[0] * B[0] + qvec[1] * B[1] + qvec[2] * B[2];
+            double qc = qvec[0] * C[0] + qvec[1] * C[1] + qvec[2] * C[2];
+            double f = amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc);
+            avg = f * f;
+        } else if (one_axis) {
+            for (int i = 0; i < n; ++i) {
+                double mu = 0.5 * (gx[i] + 1.0);
+                double st = sqrt(1.0 - mu * mu);
+                /* A-B plane direction is irrelevant for a symmetric particle */
+                double f = amplitude(p->kind, s, p->shell, p->sld, q, q * st, 0.0, q * mu);
+                avg += 0.5 * gw[i] * f * f;
+            }
+        } else {
+            for (int i = 0; i < n; ++i) {
+                double mu = 0.5 * (gx[i] + 1.0);
+                double st = sqrt(1.0 - mu * mu);
+                for (int k = 0; k < n; ++k) {
+                    double beta = 0.25 * ORC_PI * (gx[k] + 1.0);
+                    double qa = q * st * cos(beta), qb = q * st * sin(beta), qc = q * mu;
+                    double f = amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc);
+                    avg += 0.25 * gw[i] * gw[k] * f * f;
+                }
+            }
+        }
+        total += yw[j] * avg;
+    }
+    return total;
+}
+
+double orc_pq_avg(const orc_params* p, double q, const double qvec[3])
+{
+    if (p->quad_n < 1 || p->quad_n > ORC_MAX_QUAD) return NAN;
+    double gx[ORC_MAX_QUAD], gw[ORC_MAX_QUAD];
+    orc_gauss_legendre(p->quad_n, gx, gw);
+    return pq_avg_nodes(p, q, qvec, gx, gw);
+}
+
+/* Amplitude at a single explicit event, for tests: sizes scaled by y,
+ * orientation angles ang, scattering vector qvec (|qvec| = q). */
+double orc_amplitude(const orc_params* p, double q, const double qvec[3], double y,
+                     const double ang[3])
+{
+    double s[3], A[3], B[3], C[3];
+    scaled_sizes(p, y, s);
+    particle_axes(ang, A, B, C);
+    double qa = qvec[0] * A[0] + qvec[1] * A[1] + qvec[2] * A[2];
+    double qb = qvec[0] * B[0] + qvec[1] * B[1] + qvec[2] * B[2];
+    double qc = qvec[0] * C[0] + qvec[1] * C[1] + qvec[2] * C[2];
+    return amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The tracer. */
+
+typedef struct {
+    const orc_params* p;
+    double* tab_size;   /* Schulz knots (or NULL) */
+    double* tab_norm;   /* normal knots (or NULL) */
+    double one_minus_cos; /* 1 - cos(alpha) */
+    double prefactor;   /* solid angle * phi / <V> */
+    int third_block;    /* block 2 is used */
+    double gx[ORC_MAX_QUAD], gw[ORC_MAX_QUAD]; /* quadrature nodes (mode 1) */
+} orc_ctx;
+
+typedef struct {
+    int32_t pixel; /* -1: no tally */
+    double w;
+    double q;
+} orc_event;
+
+static int ctx_init(orc_ctx* cx, const orc_params* p)
+{
+    memset(cx, 0, sizeof(*cx));
+    cx->p = p;
+    int M = p->table_size;
+    if (p->mode == 0 && p->poly > 0.0) {
+        cx->tab_size = (double*)malloc(sizeof(double) * M);
+        orc_table_schulz(M, p->poly, cx->tab_size);
+    }
+    if (p->mode == 0 && p->orient_kind == 1) {
+        cx->tab_norm = (double*)malloc(sizeof(double) * M);
+        orc_table_normal(M, cx->tab_norm);
+    }
+    double sh = sin(0.5 * p->cone_alpha);
+    cx->one_minus_cos = 2.0 * sh * sh;
+    cx->prefactor = 2.0 * ORC_PI * cx->one_minus_cos * p->phi / orc_mean_volume(p);
+    cx->third_block = (p->mode == 0) && (p->poly > 0.0 || p->orient_kind != 0);
+    if (p->mode == 1) {
+        if (p->quad_n < 1 || p->quad_n > ORC_MAX_QUAD) return -1;
+        orc_gauss_legendre(p->quad_n, cx->gx, cx->gw);
+    }
+    return 0;
+}
+
+static void ctx_free(orc_ctx* cx)
+{
+    free(cx->tab_size);
+    free(cx->tab_norm);
+}
+
+static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_t e)
+{
+    const orc_params* p = cx->p;
+    orc_event ev = {-1, 0.0, 0.0};
+    uint32_t r0[4], r1[4], r2[4] = {0, 0, 0, 0};
+    neutron_block(seed, i, 0, e, r0);
+    neutron_block(seed, i, 1, e, r1);
+    if (cx->third_block) neutron_block(seed, i, 2, e, r2);
+    double u[12];
+    for (int k = 0; k < 4; ++k) {
+        u[k] = orc_uniform(r0[k]);
+        u[4 + k] = orc_uniform(r1[k]);
+        u[8 + k] = orc_uniform(r2[k]);
+    }
+
+    /* source point and slit point; the neutron flies from one to the other */
+    double src[3] = {(u[0] - 0.5) * p->src_w, (u[1] - 0.5) * p->src_h, p->src_z};
+    double slt[3] = {(u[2] - 0.5) * p->slit_w, (u[3] - 0.5) * p->slit_h, p->slit_z};
+    double d[3] = {slt[0] - src[0], slt[1] - src[1], slt[2] - src[2]};
+    double dl = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double ki[3] = {d[0] / dl, d[1] / dl, d[2] / dl};
+    double lambda = p->lambda0 * (1.0 + p->dlambda_rel * (2.0 * u[4] - 1.0));
+    double k = 2.0 * ORC_PI / lambda; /* 1/Angstrom */
+
+    /* the slab sample, centred at the origin: entry and exit along the ray */
+    double half[3] = {0.5 * p->sample_w, 0.5 * p->sample_h, 0.5 * p->sample_d};
+    double s_in = 0.0, s_out = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (ki[a] != 0.0) {
+            double t1 = (-half[a] - src[a]) / ki[a];
+            double t2 = (half[a] - src[a]) / ki[a];
+            double tl = t1 < t2 ? t1 : t2, th = t1 < t2 ? t2 : t1;
+            if (tl > s_in) s_in = tl;
+            if (th < s_out) s_out = th;
+        } else if (fabs(src[a]) > half[a]) {
+            s_out = -1.0;
+        }
+    }
+    ev.q = 0.0;
+    if (!(s_out > s_in)) return ev;
+    double len = s_out - s_in; /* metres */
+    double s = s_in + u[5] * len;
+    double rs[3] = {src[0] + s * ki[0], src[1] + s * ki[1], src[2] + s * ki[2]};
+
+    /* outgoing direction uniform in solid angle inside the cone of half-angle
+     * alpha about ki; basis orthogonal to ki after Duff et al., "Building an
+     * Orthonormal Basis, Revisited", JCGT 6(1), 2017 */
+    double t = u[6] * cx->one_minus_cos;
+    double c2 = 1.0 - t;
+    double s2 = sqrt(t * (2.0 - t));
+    double psi = 2.0 * ORC_PI * u[7];
+    double cps = cos(psi), sps = sin(psi);
+    double sg = copysign(1.0, ki[2]);
+    double aa = -1.0 / (sg + ki[2]);
+    double bb = ki[0] * ki[1] * aa;
+    double e1[3] = {1.0 + sg * ki[0] * ki[0] * aa, sg * bb, -sg * ki[0]};
+    double e2[3] = {bb, sg + ki[1] * ki[1] * aa, -ki[1]};
+    double perp[3], kf[3], qv[3];
+    for (int a = 0; a < 3; ++a) {
+        perp[a] = cps * e1[a] + sps * e2[a];
+        kf[a] = c2 * ki[a] + s2 * perp[a];
+        qv[a] = k * (-t * ki[a] + s2 * perp[a]);
+    }
+    double q = k * sqrt(2.0 * t);
+    ev.q = q;
+
+    /* size and orientation of the particle met by this neutron */
+    double y = 1.0;
+    double ang[3] = {p->orient_mean[0], p->orient_mean[1], p->orient_mean[2]};
+    double f2;
+    if (p->mode == 0) {
+        if (p->poly > 0.0) {
+            y = orc_table_lookup(cx->tab_size, p->table_size, u[8]);
+            if (y < 0.0) y = 0.0;
+        }
+        if (p->orient_kind == 1) {
+            for (int a = 0; a < 3; ++a)
+                ang[a] = p->orient_mean[a]
+                       + p->orient_sigma[a] * orc_table_lookup(cx->tab_norm, p->table_size, u[9 + a]);
+        } else if (p->orient_kind == 2) {
+            ang[0] = acos(2.0 * u[9] - 1.0);
+            ang[1] = 2.0 * ORC_PI * u[10];
+            ang[2] = 2.0 * ORC_PI * u[11];
+        } else if (p->orient_kind == 3) {
+            ang[0] = ORC_PI * u[9];
+            ang[1] = 2.0 * ORC_PI * u[10];
+            ang[2] = 2.0 * ORC_PI * u[11];
+        }
+        double f = orc_amplitude(p, q, qv, y, ang);
+        f2 = f * f;
+    } else {
+        f2 = pq_avg_nodes(p, q, qv, cx->gx, cx->gw);
+    }
+    double sq = (p->sq_phi > 0.0) ? orc_py_sq(q, p->sq_radius, p->sq_phi) : 1.0;
+    double w = len * 1e10 * cx->prefactor * f2 * sq;
+
+    /* straight flight to the detector plane and the pixel hit */
+    if (!(kf[2] > 0.0)) return ev;
+    double sd = (p->det_z - rs[2]) / kf[2];
+    double xd = rs[0] + sd * kf[0];
+    double yd = rs[1] + sd * kf[1];
+    double fx = floor((xd + 0.5 * p->det_w) / (p->det_w / p->nx));
+    double fy = floor((yd + 0.5 * p->det_h) / (p->det_h / p->ny));
+    if (fx < 0.0 || fx >= p->nx || fy < 0.0 || fy >= p->ny) return ev;
+    ev.pixel = (int32_t)fy * p->nx + (int32_t)fx;
+    ev.w = w;
+    return ev;
+}
+
+int orc_trace_debug(const orc_params* p, uint64_t first, uint64_t n, uint64_t seed,
+                    uint32_t exp_id, int32_t* pixel, double* w, double* q)
+{
+    orc_ctx cx;
+    if (ctx_init(&cx, p) != 0) return -1;
+    for (uint64_t j = 0; j < n; ++j) {
+        orc_event ev = trace_one(&cx, first + j, seed, exp_id);
+        if (pixel) pixel[j] = ev.pixel;
+        if (w) w[j] = ev.w;
+        if (q) q[j] = ev.q;
+    }
+    ctx_free(&cx);
+    return 0;
+}
+
+typedef struct {
+    const orc_ctx* cx;
+    uint64_t first, n, seed;
+    uint32_t exp_id;
+    double* det;
+    double* det_w2;
+    uint64_t* det_count;
+} orc_job;
+
+static void* run_job(void* arg)
+{
+    orc_job* jb = (orc_job*)arg;
+    for (uint64_t j = 0; j < jb->n; ++j) {
+        orc_event ev = trace_one(jb->cx, jb->first + j, jb->seed, jb->exp_id);
+        if (ev.pixel >= 0) {
+            jb->det[ev.pixel] += ev.w;
+            if (jb->det_w2) jb->det_w2[ev.pixel] += ev.w * ev.w;
+            if (jb->det_count) jb->det_count[ev.pixel] += 1;
+        }
+    }
+    return NULL;
+}
+
+/* Traces neutrons first .. first+n-1 and writes the summed detector (ny*nx,
+ * row-major, FP64) into det; det_w2 (sum of w^2) and det_count (hits) are
+ * optional.  The range is split into nthreads contiguous parts with private
+ * detectors that are merged in thread order. */
+int orc_trace(const orc_params* p, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
+              int32_t nthreads, double* det, double* det_w2, uint64_t* det_count)
+{
+    if (nthreads < 1) nthreads = 1;
+    size_t npix = (size_t)p->nx * (size_t)p->ny;
+    orc_ctx cx;
+    if (ctx_init(&cx, p) != 0) return -1;
+    orc_job* jobs = (orc_job*)calloc(nthreads, sizeof(orc_job));
+    pthread_t* th = (pthread_t*)calloc(nthreads, sizeof(pthread_t));
+    uint64_t start = first;
+    for (int t = 0; t < nthreads; ++t) {
+        uint64_t cnt = n / nthreads + ((uint64_t)t < n % nthreads ? 1 : 0);
+        jobs[t].cx = &cx;
+        jobs[t].first = start;
+        jobs[t].n = cnt;
+        jobs[t].seed = seed;
+        jobs[t].exp_id = exp_id;
+        jobs[t].det = (double*)calloc(npix, sizeof(double));
+        jobs[t].det_w2 = det_w2 ? (double*)calloc(npix, sizeof(double)) : NULL;
+        jobs[t].det_count = det_count ? (uint64_t*)calloc(npix, sizeof(uint64_t)) : NULL;
+        start += cnt;
+    }
+    for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, run_job, &jobs[t]);
+    run_job(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+    memset(det, 0, npix * sizeof(double));
+    if (det_w2) memset(det_w2, 0, npix * sizeof(double));
+    if (det_count) memset(det_count, 0, npix * sizeof(uint64_t));
+    for (int t = 0; t < nthreads; ++t) {
+        for (size_t k = 0; k < npix; ++k) {
+            det[k] += jobs[t].det[k];
+            if (det_w2) det_w2[k] += jobs[t].det_w2[k];
+            if (det_count) det_count[k] += jobs[t].det_count[k];
+        }
+        free(jobs[t].det);
+        free(jobs[t].det_w2);
+        free(jobs[t].det_count);
+    }
+    free(jobs);
+    free(th);
+    ctx_free(&cx);
+    return 0;
+}

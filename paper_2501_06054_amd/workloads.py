@@ -1,0 +1,192 @@
+"""Seeded synthetic workloads for the SANS sample tracer.
+
+This module only *describes* inputs: parameter sets of the instrument and the
+sample, neutron counts, seeds and the seeded generator of the batched
+high-throughput experiment set.  It holds none of the method's arithmetic, so
+that the HIP library's binding and the CPU oracle can both consume the same
+inputs without sharing code.
+
+Units: instrument geometry in metres, wavelength and sample sizes in
+Angstrom, scattering-length densities in 1/Angstrom^2, angles in radians.
+
+The paper's own instrument (the KWS-1 model, a monochromatic source, guides,
+slits, the sample and a 2D position-sensitive detector; Methods, end of
+"Form factor and structure factor models") is not published with it, so a
+synthetic stand-in of the same structure is used: a square source 8 m
+upstream, a square slit at the sample face, a 1 mm slab sample and a square
+area detector 5 m downstream.
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+KINDS = ("sphere", "core_shell", "cylinder", "ellipsoid", "parallelepiped")
+ORIENT_KINDS = ("fixed", "gaussian", "isotropic", "uniform_angles")
+MODES = ("mc", "quad", "surrogate")
+
+DEG = math.pi / 180.0
+
+#: The common instrument: 10x10 mm source at z = -8 m, 5x5 mm slit on the
+#: sample front face, wavelength uniform in 6 A +- 5 %, scattering directions
+#: uniform inside a 0.05 rad cone, 10x10x1 mm slab, 0.6x0.6 m detector at 5 m.
+INSTRUMENT = dict(
+    src_w=0.010, src_h=0.010, src_z=-8.0,
+    slit_w=0.005, slit_h=0.005, slit_z=-0.0005,
+    lambda0=6.0, dlambda_rel=0.05, cone_alpha=0.05,
+    sample_w=0.010, sample_h=0.010, sample_d=0.001,
+    det_w=0.6, det_h=0.6, det_z=5.0,
+    nx=128, ny=128,
+)
+
+SAMPLE_DEFAULTS = dict(
+    kind="sphere", mode="mc",
+    size=(50.0, 0.0, 0.0), shell=0.0, sld=(1e-6, 0.0, 0.0),
+    phi=0.01, sq_phi=0.0, sq_radius=0.0,
+    poly=0.0, poly_mask=1,
+    orient_kind="fixed", orient_mean=(0.0, 0.0, 0.0), orient_sigma=(0.0, 0.0, 0.0),
+    table_size=4096, quad_n=76,
+)
+
+
+def params(**over) -> dict:
+    """A full parameter dict: defaults, then the instrument, then overrides."""
+    p = dict(SAMPLE_DEFAULTS)
+    p.update(INSTRUMENT)
+    for k, v in over.items():
+        if k not in p:
+            raise KeyError(f"unknown parameter {k!r}")
+        p[k] = v
+    for k in ("size", "sld", "orient_mean", "orient_sigma"):
+        p[k] = tuple(float(x) for x in p[k])
+    return p
+
+
+# --------------------------------------------------------------------------
+# The named workloads.  n is the neutron count the workload is quoted on.
+
+def tiny_sphere() -> dict:
+    """Monodisperse sphere R = 50 A, contrast 1e-6 /A^2, volume fraction 0.01,
+    no structure factor, 128x128 detector, 1e6 neutrons, seed 1."""
+    return dict(name="tiny_sphere", n=10**6, seed=1, exp_id=0,
+                params=params(kind="sphere", size=(50.0, 0, 0), sld=(1e-6, 0, 0), phi=0.01))
+
+
+def coreshell_py() -> dict:
+    """Core-shell sphere: Schulz core radius (mean 40 A, sigma/mean 0.2) with a
+    10 A shell, SLD core/shell/solvent 1e-6/3e-6/6.3e-6, hard-sphere
+    Percus-Yevick S(Q) at volume fraction 0.2 (effective radius 50 A),
+    256x256 detector, 1e8 neutrons, seed 2."""
+    return dict(name="coreshell_py", n=10**8, seed=2, exp_id=0,
+                params=params(kind="core_shell", size=(40.0, 0, 0), shell=10.0,
+                              sld=(1e-6, 3e-6, 6.3e-6), phi=0.2, sq_phi=0.2, sq_radius=50.0,
+                              poly=0.2, poly_mask=1, nx=256, ny=256))
+
+
+def oriented_cylinder() -> dict:
+    """Cylinders R = 20 A, L = 400 A, axis along the beam-perpendicular x axis
+    with Gaussian angular spread 10 deg, 256x256 detector, 1e9 neutrons."""
+    return dict(name="oriented_cylinder", n=10**9, seed=3, exp_id=0,
+                params=params(kind="cylinder", size=(20.0, 400.0, 0), sld=(1e-6, 0, 0),
+                              phi=0.01, orient_kind="gaussian",
+                              orient_mean=(90 * DEG, 0.0, 0.0),
+                              orient_sigma=(10 * DEG, 10 * DEG, 0.0), nx=256, ny=256))
+
+
+def oriented_ellipsoid() -> dict:
+    """Triaxial ellipsoids with semi-axes 20/40/120 A (A along y, B along z,
+    C along x), Gaussian angular spread 10 deg, 256x256, 1e9 neutrons."""
+    return dict(name="oriented_ellipsoid", n=10**9, seed=4, exp_id=0,
+                params=params(kind="ellipsoid", size=(20.0, 40.0, 120.0), sld=(1e-6, 0, 0),
+                              phi=0.01, orient_kind="gaussian",
+                              orient_mean=(90 * DEG, 0.0, 90 * DEG),
+                              orient_sigma=(10 * DEG, 10 * DEG, 10 * DEG), nx=256, ny=256))
+
+
+def quad_parallelepiped() -> dict:
+    """Isotropically oriented parallelepipeds 20x40x120 A whose orientation
+    average is taken by 76x76 Gauss-Legendre quadrature per neutron (exact
+    average mode), 128x128 detector, seed 6."""
+    return dict(name="quad_parallelepiped", n=10**8, seed=6, exp_id=0,
+                params=params(kind="parallelepiped", mode="quad", size=(20.0, 40.0, 120.0),
+                              sld=(1e-6, 0, 0), phi=0.01, orient_kind="isotropic"))
+
+
+def quad_spheroid() -> dict:
+    """Polydisperse, isotropically oriented spheroids (a = b = 20 A, c = 60 A,
+    Schulz width 0.2 on all axes) averaged by 76x76 (mu, size) quadrature."""
+    return dict(name="quad_spheroid", n=10**8, seed=7, exp_id=0,
+                params=params(kind="ellipsoid", mode="quad", size=(20.0, 20.0, 60.0),
+                              sld=(1e-6, 0, 0), phi=0.01, poly=0.2, poly_mask=7,
+                              orient_kind="isotropic"))
+
+
+WORKLOADS = {
+    "tiny_sphere": tiny_sphere,
+    "coreshell_py": coreshell_py,
+    "oriented_cylinder": oriented_cylinder,
+    "oriented_ellipsoid": oriented_ellipsoid,
+    "quad_parallelepiped": quad_parallelepiped,
+    "quad_spheroid": quad_spheroid,
+}
+
+
+def workload(name: str) -> dict:
+    return copy.deepcopy(WORKLOADS[name]())
+
+
+# --------------------------------------------------------------------------
+# The batched high-throughput set: 4096 virtual experiments.
+
+def batch_experiments(n_exp: int = 4096, seed: int = 4096, nx: int = 128,
+                      n_lo: float = 1e5, n_hi: float = 1e7) -> list[dict]:
+    """Seeded experiment list (NumPy PCG64).  Model uniform over the five
+    kinds; characteristic size log-uniform in [10, 200] A; secondary sizes are
+    the size times a log-uniform aspect ratio in [1, 10]; core-shell shell =
+    0.25 size; Schulz width uniform in [0, 0.3] applied to all sizes; volume
+    fraction uniform in [0, 0.3] for both the number density and the
+    hard-sphere S(Q), whose radius is the equal-volume sphere radius;
+    isotropic orientation; neutron count log-uniform in [n_lo, n_hi]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for e in range(n_exp):
+        kind = KINDS[int(rng.integers(0, 5))]
+        s = float(np.exp(rng.uniform(math.log(10.0), math.log(200.0))))
+        r1 = float(np.exp(rng.uniform(0.0, math.log(10.0))))
+        r2 = float(np.exp(rng.uniform(0.0, math.log(10.0))))
+        poly = float(rng.uniform(0.0, 0.3))
+        phi = float(rng.uniform(0.0, 0.3))
+        n = int(round(float(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi))))))
+        shell = 0.0
+        sld = (1e-6, 0.0, 0.0)
+        if kind == "sphere":
+            size = (s, 0.0, 0.0)
+            mask = 1
+            req = s
+        elif kind == "core_shell":
+            size = (s, 0.0, 0.0)
+            shell = 0.25 * s
+            sld = (1e-6, 3e-6, 6.3e-6)
+            mask = 1
+            req = s + shell
+        elif kind == "cylinder":
+            size = (s, s * r1, 0.0)
+            mask = 3
+            req = (0.75 * s * s * s * r1) ** (1.0 / 3.0)
+        elif kind == "ellipsoid":
+            size = (s, s * r1, s * r2)
+            mask = 7
+            req = (s * s * r1 * s * r2) ** (1.0 / 3.0)
+        else:
+            size = (s, s * r1, s * r2)
+            mask = 7
+            req = (s * s * r1 * s * r2 * 3.0 / (4.0 * math.pi)) ** (1.0 / 3.0)
+        p = params(kind=kind, size=size, shell=shell, sld=sld, phi=phi, sq_phi=phi,
+                   sq_radius=req, poly=poly, poly_mask=mask,
+                   orient_kind="isotropic" if kind in ("cylinder", "ellipsoid",
+                                                       "parallelepiped") else "fixed",
+                   nx=nx, ny=nx)
+        out.append(dict(exp_id=e, n=n, seed=5, params=p))
+    return out

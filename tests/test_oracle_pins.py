@@ -1,0 +1,448 @@
+"""Pins of the FP64 oracle to things other than itself: published known-answer
+vectors, closed forms, special cases that reduce to library routines
+(scipy/numpy/mpmath), invariants of the geometry and unbiasedness of the
+Monte Carlo estimator against deterministic quadrature."""
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.special as sp
+import scipy.stats as st
+
+from paper_2501_06054_amd import workloads as W
+from tests.conftest import GOLDEN, golden_values
+
+SV = golden_values("special_values.txt")
+
+
+# ----------------------------------------------------------------- Philox
+
+def test_philox_known_answers(orc):
+    rows = []
+    with open(f"{GOLDEN}/philox4x32_10_kat.txt") as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(x, 16) for x in line.split()])
+    assert len(rows) == 3
+    for r in rows:
+        out = orc.philox(r[0:4], r[4:6])
+        assert [int(x) for x in out] == r[6:10]
+
+
+def test_philox_stream_counter_layout(orc):
+    # block b of neutron i in experiment e uses counter (lo i, hi i, b, e) and
+    # key (lo seed, hi seed); the stream of a far neutron index uses hi i.
+    seed, i, e = 0x123456789ABCDEF0, (1 << 40) + 17, 7
+    s = orc.philox_stream(seed, i, 1, 3, e)
+    for b in range(3):
+        ref = orc.philox([i & 0xFFFFFFFF, i >> 32, b, e], [seed & 0xFFFFFFFF, seed >> 32])
+        assert list(s[0, b]) == list(ref)
+
+
+def test_uniform_mapping(orc):
+    assert orc.uniform(0) == 0.5 * 2.0**-32
+    assert orc.uniform(0xFFFFFFFF) == 1.0 - 0.5 * 2.0**-32
+    assert 0.0 < orc.uniform(0) < orc.uniform(1) < 1.0
+
+
+# ----------------------------------------------------------------- tables
+
+def test_normal_quantile_vs_library(orc):
+    for u in [1e-6, 1.2e-4, 0.01, 0.3, 0.5, 0.77, 0.999, 1 - 1e-5]:
+        assert orc.normal_quantile(u) == pytest.approx(sp.ndtri(u), rel=1e-12, abs=1e-13)
+
+
+def test_gamma_p_vs_library(orc):
+    for a in [0.5, 2.0, 11.1, 25.0, 400.0, 10000.0]:
+        for x in [0.1 * a, 0.7 * a, a, 1.3 * a, 2.5 * a]:
+            assert orc.gamma_p(a, x) == pytest.approx(sp.gammainc(a, x), rel=1e-11, abs=1e-14)
+
+
+def test_schulz_quantile_vs_library(orc):
+    for p in [0.02, 0.1, 0.2, 0.3]:
+        a = 1.0 / p**2
+        for u in [1e-4, 0.05, 0.5, 0.93, 1 - 1e-4]:
+            ref = st.gamma.ppf(u, a, scale=1.0 / a)
+            assert orc.schulz_quantile(u, p) == pytest.approx(ref, rel=1e-10)
+
+
+def test_table_lookup_interpolates_knots(orc):
+    M = 64
+    knots = orc.table_normal(M)
+    for k in [0, 5, 31, 63]:
+        assert orc.table_lookup(knots, (k + 0.5) / M) == pytest.approx(knots[k], abs=1e-15)
+    # halfway between two knots -> their mean; linear extrapolation at the ends
+    assert orc.table_lookup(knots, 10.0 / M) == pytest.approx(0.5 * (knots[9] + knots[10]))
+    assert orc.table_lookup(knots, 0.0) == pytest.approx(knots[0] - 0.5 * (knots[1] - knots[0]))
+    assert orc.table_lookup(knots, 1.0) == pytest.approx(knots[-1] + 0.5 * (knots[-1] - knots[-2]))
+
+
+def test_schulz_table_moments(orc):
+    # integrate the lookup over u in (0, 1): the moments of the tabulated
+    # distribution are the Schulz closed-form moments up to the tails
+    M = 4096
+    knots = orc.table_schulz(M, 0.2)
+    u = (np.arange(200000) + 0.5) / 200000
+    y = np.array([orc.table_lookup(knots, x) for x in u[::10]])
+    assert np.mean(y) == pytest.approx(1.0, abs=2e-4)
+    assert np.mean(y**3) == pytest.approx(SV["schulz_m3_p0.2"], rel=3e-4)
+    assert np.mean(y**6) == pytest.approx(SV["schulz_m6_p0.2"], rel=2e-3)
+
+
+# ----------------------------------------------------------------- shapes
+
+def test_sphere_amplitude(orc):
+    assert orc.sph(0.0) == 1.0
+    for k in range(1, 5):
+        assert abs(orc.sph(SV[f"sph_zero_{k}"])) < 1e-14
+    for x in [1e-3, 0.05, 0.0999, 0.1001, 0.5, 3.0, 40.0]:
+        ref = 3.0 * sp.spherical_jn(1, x) / x
+        assert orc.sph(x) == pytest.approx(ref, rel=1e-12, abs=1e-16)
+    # Guinier: P(q) = sph(qR)^2 ~ 1 - (qR)^2/5 at small qR (Rg^2 = 3R^2/5)
+    x = 1e-3
+    assert (1.0 - orc.sph(x) ** 2) / x**2 == pytest.approx(1.0 / 5.0, rel=1e-5)
+
+
+def test_lambda1(orc):
+    assert orc.lambda1(0.0) == 1.0
+    for k in (1, 2):
+        assert abs(orc.lambda1(SV[f"j1_zero_{k}"])) < 1e-15
+    for x in [1e-5, 9e-4, 1.1e-3, 0.4, 2.9, 12.0, 150.0]:
+        assert orc.lambda1(x) == pytest.approx(2 * sp.j1(x) / x, rel=1e-13, abs=1e-17)
+
+
+def test_sinc(orc):
+    assert orc.sinc(0.0) == 1.0
+    for n in (1, 2, 7):
+        assert abs(orc.sinc(n * math.pi)) < 1e-15
+    for x in [1e-6, 0.3, 5.0]:
+        assert orc.sinc(x) == pytest.approx(np.sinc(x / np.pi), rel=1e-14)
+
+
+# ----------------------------------------------------------------- S(Q)
+
+def _py_by_integration(x, phi):
+    # independent route: S = 1/(1 - n c^(q)) with the Percus-Yevick direct
+    # correlation function c(r) = -(alpha + beta s + gamma s^3), s = r/sigma < 1,
+    # Fourier-transformed numerically: -n c^ = 24 phi / x * int_0^1
+    # (alpha s + beta s^2 + gamma s^4) sin(x s) ds
+    om4 = (1 - phi) ** 4
+    alpha = (1 + 2 * phi) ** 2 / om4
+    beta = -6 * phi * (1 + phi / 2) ** 2 / om4
+    gamma = phi * alpha / 2
+    if x == 0.0:
+        g_over_x = alpha / 3 + beta / 4 + gamma / 6
+    else:
+        val, _ = si.quad(lambda s: (alpha * s + beta * s * s + gamma * s**4) * math.sin(x * s),
+                         0.0, 1.0, epsabs=1e-15, epsrel=1e-13, limit=200)
+        g_over_x = val / x
+    return 1.0 / (1.0 + 24 * phi * g_over_x)
+
+
+def test_py_s0_closed_form(orc):
+    assert orc.py_sq(0.0, 50.0, 0.2) == pytest.approx(SV["py_s0_phi0.2"], rel=1e-14)
+    for phi in [0.01, 0.1, 0.3, 0.45]:
+        assert orc.py_sq(0.0, 10.0, phi) == pytest.approx((1 - phi) ** 4 / (1 + 2 * phi) ** 2,
+                                                          rel=1e-13)
+
+
+@pytest.mark.parametrize("phi", [0.05, 0.2, 0.35])
+def test_py_vs_direct_correlation_transform(orc, phi):
+    R = 50.0
+    for x in [1e-4, 0.02, 0.5, 0.99, 1.01, 2.0, 4.4, 9.0, 30.0]:
+        q = x / (2 * R)
+        assert orc.py_sq(q, R, phi) == pytest.approx(_py_by_integration(x, phi), rel=1e-10)
+
+
+def test_py_limits(orc):
+    assert orc.py_sq(0.3, 50.0, 0.0) == 1.0
+    assert orc.py_sq(100.0, 50.0, 0.2) == pytest.approx(1.0, abs=1e-4)
+
+
+# ----------------------------------------------------------------- amplitudes
+
+def test_gauss_legendre_vs_library(orc):
+    for n in (1, 2, 5, 76, 150):
+        x, w = orc.gauss_legendre(n)
+        xr, wr = np.polynomial.legendre.leggauss(n)
+        assert np.allclose(x, xr, rtol=0, atol=1e-14)
+        assert np.allclose(w, wr, rtol=1e-11, atol=1e-15)
+
+
+def test_mean_volume_closed_forms(orc):
+    cs = W.workload("coreshell_py")["params"]
+    # 4pi/3 (R^3 <y^3> + 3 R^2 t <y^2> + 3 R t^2 + t^3), R = 40, t = 10, z = 24
+    ref = 4 * math.pi / 3 * (40**3 * 1.1232 + 3 * 1600 * 10 * 1.04 + 3 * 40 * 100 + 1000)
+    assert orc.mean_volume(cs) == pytest.approx(ref, rel=1e-13)
+    sph = W.workload("tiny_sphere")["params"]
+    assert orc.mean_volume(sph) == pytest.approx(4 * math.pi / 3 * 50**3, rel=1e-15)
+    cyl = W.params(kind="cylinder", size=(20, 400, 0), poly=0.1, poly_mask=3)
+    a = 100.0
+    assert orc.mean_volume(cyl) == pytest.approx(
+        math.pi * 20**2 * 400 * (1 + 1 / a) * (1 + 2 / a), rel=1e-13)
+
+
+def test_core_shell_reduces_to_sphere(orc):
+    q, qv = 0.031, (0.031, 0.0, 0.0)
+    # equal core and shell density: one sphere of radius R + t
+    cs = W.params(kind="core_shell", size=(40, 0, 0), shell=10, sld=(3e-6, 3e-6, 1e-6))
+    sph = W.params(kind="sphere", size=(50, 0, 0), sld=(3e-6, 0, 1e-6))
+    assert orc.amplitude(cs, q, qv) == pytest.approx(orc.amplitude(sph, q, qv), rel=1e-13)
+    # zero shell thickness: a sphere of the core radius with core-solvent contrast
+    cs0 = W.params(kind="core_shell", size=(40, 0, 0), shell=0, sld=(3e-6, 5e-6, 1e-6))
+    sph0 = W.params(kind="sphere", size=(40, 0, 0), sld=(3e-6, 0, 1e-6))
+    assert orc.amplitude(cs0, q, qv) == pytest.approx(orc.amplitude(sph0, q, qv), rel=1e-13)
+    # forward amplitude: sum of contrast x volume (configs' core-shell at the mean radius)
+    cs1 = W.workload("coreshell_py")["params"]
+    f0 = orc.amplitude(cs1, 0.0, (0, 0, 0))
+    ref = (1e-6 - 3e-6) * 4 * math.pi / 3 * 40**3 + (3e-6 - 6.3e-6) * 4 * math.pi / 3 * 50**3
+    assert f0 == pytest.approx(ref, rel=1e-14)
+    assert f0 == pytest.approx(-2.264041, rel=1e-6)
+
+
+def test_ellipsoid_reduces_to_sphere(orc):
+    ell = W.params(kind="ellipsoid", size=(30, 30, 30))
+    sph = W.params(kind="sphere", size=(30, 0, 0))
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        v = rng.normal(size=3)
+        v *= 0.04 / np.linalg.norm(v)
+        ang = rng.uniform(0, 6, size=3)
+        assert orc.amplitude(ell, 0.04, v, angles=ang) == pytest.approx(
+            orc.amplitude(sph, 0.04, v), rel=1e-12)
+
+
+def test_cylinder_orientation_geometry(orc):
+    R, L = 20.0, 400.0
+    cyl = W.params(kind="cylinder", size=(R, L, 0), orient_mean=(math.pi / 2, 0, 0))
+    V = math.pi * R * R * L * 1e-6
+    # axis along x: Q along y sees only the Bessel factor -> zero at the J1 zero
+    q = SV["j1_zero_1"] / R
+    assert abs(orc.amplitude(cyl, q, (0, q, 0))) < 1e-15 * V
+    # Q along the axis sees only the sinc factor -> zeros at Q L / 2 = n pi
+    q = 2 * math.pi / L
+    assert abs(orc.amplitude(cyl, q, (q, 0, 0))) < 1e-15 * V
+    q = 0.01
+    assert orc.amplitude(cyl, q, (q, 0, 0)) == pytest.approx(V * np.sinc(q * L / 2 / np.pi))
+    assert orc.amplitude(cyl, q, (0, 0, q)) == pytest.approx(V * 2 * sp.j1(q * R) / (q * R))
+
+
+def test_particle_axes_convention(orc):
+    # angles (90, 0, 90) deg put A on y, B on z, C on x
+    a, b, c = 20.0, 40.0, 120.0
+    par = W.params(kind="parallelepiped", size=(a, b, c),
+                   orient_mean=(math.pi / 2, 0, math.pi / 2))
+    q = 0.05
+    for axis, edge in ((1, a), (2, b), (0, c)):
+        v = [0.0, 0.0, 0.0]
+        v[axis] = q
+        ref = 1e-6 * a * b * c * np.sinc(q * edge / 2 / np.pi)
+        assert orc.amplitude(par, q, v) == pytest.approx(ref, rel=1e-13)
+
+
+def test_parallelepiped_cube_rod(orc):
+    # a cube oriented with its edges on the lab axes; a long rod's sinc along C
+    cube = W.params(kind="parallelepiped", size=(30, 30, 30))
+    q = 0.07
+    v = np.array([1.0, 2.0, 2.0]) / 3 * q
+    ref = 1e-6 * 27000 * np.prod(np.sinc(v * 30 / 2 / np.pi))
+    assert orc.amplitude(cube, q, v, angles=(0, 0, 0)) == pytest.approx(ref, rel=1e-13)
+
+
+@pytest.mark.parametrize("kind,size,rg2", [
+    ("cylinder", (20, 400, 0), 20**2 / 2 + 400**2 / 12),
+    ("ellipsoid", (20, 40, 120), (20**2 + 40**2 + 120**2) / 5),
+    ("parallelepiped", (20, 40, 120), (20**2 + 40**2 + 120**2) / 12),
+    ("ellipsoid", (20, 20, 60), (2 * 20**2 + 60**2) / 5),
+])
+def test_isotropic_average_guinier(orc, kind, size, rg2):
+    # the orientation-averaged form factor obeys P = 1 - q^2 Rg^2 / 3 + O(q^4)
+    p = W.params(kind=kind, size=size, orient_kind="isotropic", mode="quad")
+    v2 = (orc.amplitude(p, 0.0, (0, 0, 0))) ** 2
+    q = 2e-4
+    pbar = orc.pq_avg(p, q) / v2
+    assert (1 - pbar) / q**2 == pytest.approx(rg2 / 3, rel=2e-3)
+    assert orc.pq_avg(p, 0.0) / v2 == pytest.approx(1.0, rel=1e-13)
+
+
+def test_isotropic_average_converged(orc):
+    # 76x76 Gauss-Legendre against 150x150 on the parallelepiped at large qL
+    p76 = W.params(kind="parallelepiped", size=(20, 40, 120), orient_kind="isotropic", mode="quad")
+    p150 = dict(p76, quad_n=150)
+    for q in [0.01, 0.05, 0.1]:
+        assert orc.pq_avg(p76, q) == pytest.approx(orc.pq_avg(p150, q), rel=1e-9)
+
+
+def test_sphere_orientation_average_is_trivial(orc):
+    # the 2D orientation average of an ellipsoid with a = b = c equals the sphere
+    ell = W.params(kind="ellipsoid", size=(25, 25.0000001, 25), orient_kind="isotropic", mode="quad")
+    sph = W.params(kind="sphere", size=(25, 0, 0), mode="quad")
+    for q in [0.02, 0.2]:
+        assert orc.pq_avg(ell, q) == pytest.approx(orc.pq_avg(sph, q), rel=1e-6)
+
+
+def test_schulz_size_average_moments(orc):
+    # <F^2>(q=0) = drho^2 V0^2 <y^(2k)>, here the spheroid with all axes scaled (k = 3)
+    p = W.workload("quad_spheroid")["params"]
+    v0 = 1e-6 * 4 * math.pi / 3 * 20 * 20 * 60
+    a = 1 / 0.2**2
+    m6 = np.prod([(a + j) / a for j in range(6)])
+    assert orc.pq_avg(p, 0.0) == pytest.approx(v0 * v0 * m6, rel=1e-6)
+
+
+# ----------------------------------------------------------------- tracer
+
+def test_every_neutron_hits_sample_and_detector(orc):
+    # tiny sphere: the beam is narrower than the sample and the cone (5 m x
+    # tan 0.05 ~ 0.25 m) fits inside the 0.6 m detector
+    p = W.workload("tiny_sphere")["params"]
+    pix, w, q = orc.trace_debug(p, 20000, 1)
+    assert np.all(pix >= 0)
+    assert np.all(w > 0)
+    # |Q| = k sqrt(2 t), 1 - cos(alpha) >= t: the largest reachable |Q|
+    kmax = 2 * math.pi / (6.0 * 0.95)
+    assert q.max() <= kmax * math.sqrt(2 * (1 - math.cos(0.05))) * (1 + 1e-12)
+
+
+def test_cone_sampling_uniform_in_solid_angle(orc):
+    # with a single wavelength, t = q^2 / (2 k^2) = 1 - cos(2 theta) must be
+    # uniform on [0, 1 - cos(alpha)]
+    p = dict(W.workload("tiny_sphere")["params"], dlambda_rel=0.0)
+    _, _, q = orc.trace_debug(p, 40000, 11)
+    k = 2 * math.pi / 6.0
+    t = q**2 / (2 * k * k) / (1 - math.cos(0.05))
+    assert st.kstest(t, "uniform").pvalue > 1e-3
+
+
+def test_detector_ring_matches_scattering_angle(orc):
+    # a pencil beam (no source or slit size): pixel radius <-> 2 theta
+    p = dict(W.workload("tiny_sphere")["params"], dlambda_rel=0.0, src_w=0.0, src_h=0.0,
+             slit_w=0.0, slit_h=0.0, sample_d=1e-9, nx=600, ny=600)
+    pix, _, q = orc.trace_debug(p, 5000, 5)
+    ix, iy = pix % 600, pix // 600
+    x = (ix + 0.5) * 1e-3 - 0.3
+    y = (iy + 0.5) * 1e-3 - 0.3
+    two_theta = np.arctan(np.hypot(x, y) / 5.0)
+    k = 2 * math.pi / 6.0
+    q_geo = 2 * k * np.sin(two_theta / 2)
+    assert np.max(np.abs(q_geo - q)) < 2 * k * 1e-3 / 5.0
+
+
+def _sphere_expected_mean_weight(p, nodes=400):
+    # E[w] = l * solid angle * n * drho^2 V^2 * E[P(k sqrt(2t))] with
+    # lambda ~ U[l0(1-d), l0(1+d)], t ~ U[0, 1-cos alpha]; l = slab thickness
+    # (the beam divergence below 1 mrad changes l by < 1e-6)
+    R, l0, d, alpha = p["size"][0], p["lambda0"], p["dlambda_rel"], p["cone_alpha"]
+    omc = 1 - math.cos(alpha)
+    V = 4 * math.pi / 3 * R**3
+    xs, ws = np.polynomial.legendre.leggauss(nodes)
+    lam = l0 * (1 + d * xs)
+    t = 0.5 * omc * (xs + 1)
+    L, T = np.meshgrid(lam, t, indexing="ij")
+    x = 2 * math.pi / L * np.sqrt(2 * T) * R
+    P = (3 * sp.spherical_jn(1, x) / x) ** 2
+    EP = 0.25 * np.einsum("i,j,ij->", ws, ws, P)
+    return p["sample_d"] * 1e10 * 2 * math.pi * omc * p["phi"] / V * (p["sld"][0] * V) ** 2 * EP
+
+
+def test_sphere_total_intensity_unbiased(orc):
+    p = W.workload("tiny_sphere")["params"]
+    n = 1_000_000
+    det, w2, cnt = orc.trace(p, n, 1, nthreads=8, with_w2=True, with_count=True)
+    assert cnt.sum() == n
+    mean = det.sum() / n
+    sigma = math.sqrt(max(w2.sum() / n - mean**2, 0.0) / n)
+    ref = _sphere_expected_mean_weight(p)
+    assert abs(mean - ref) < 4 * sigma
+    # the forward weight of this configuration (q -> 0): l drho^2 V phi solid angle
+    assert ref < 4.1115e-4 * 1.0001
+
+
+def test_coreshell_total_intensity_unbiased(orc):
+    # the Monte Carlo total equals the deterministic expectation over lambda,
+    # t and the Schulz size distribution of S(q) F^2
+    wl = W.workload("coreshell_py")
+    p = wl["params"]
+    n = 400_000
+    det, w2, _ = orc.trace(p, n, 2, nthreads=8, with_w2=True, with_count=True)
+    mean = det.sum() / n
+    sigma = math.sqrt(max(w2.sum() / n - mean**2, 0.0) / n)
+
+    R, t_sh, (r1, r2, r3) = 40.0, 10.0, p["sld"]
+    pw = p["poly"]
+    a = 1 / pw**2
+    omc = 1 - math.cos(p["cone_alpha"])
+
+    def sph(x):
+        return 3 * sp.spherical_jn(1, x) / x
+
+    ys, yw = np.polynomial.legendre.leggauss(200)
+    ylo, yhi = 1e-6, 3.0
+    yv = 0.5 * (yhi - ylo) * ys + 0.5 * (yhi + ylo)
+    ywt = 0.5 * (yhi - ylo) * yw * st.gamma.pdf(yv, a, scale=1 / a)
+    xs, ws = np.polynomial.legendre.leggauss(120)
+    tot = 0.0
+    for xl, wl_ in zip(xs, ws):
+        lam = p["lambda0"] * (1 + p["dlambda_rel"] * xl)
+        for xt, wt in zip(xs, ws):
+            tt = 0.5 * omc * (xt + 1)
+            q = 2 * math.pi / lam * math.sqrt(2 * tt)
+            rc = R * yv
+            ro = rc + t_sh
+            F = (r1 - r2) * 4 * math.pi / 3 * rc**3 * sph(q * rc) + \
+                (r2 - r3) * 4 * math.pi / 3 * ro**3 * sph(q * ro)
+            S = _py_by_integration(2 * q * p["sq_radius"], p["sq_phi"])
+            tot += 0.25 * wl_ * wt * S * np.sum(ywt * F * F)
+    vbar = 4 * math.pi / 3 * (R**3 * 1.1232 + 3 * R * R * t_sh * 1.04 + 3 * R * t_sh**2 + t_sh**3)
+    ref = p["sample_d"] * 1e10 * 2 * math.pi * omc * p["phi"] / vbar * tot
+    assert abs(mean - ref) < 4 * sigma
+
+
+@pytest.mark.parametrize("kind,size", [("cylinder", (20, 400, 0)),
+                                       ("parallelepiped", (20, 40, 120)),
+                                       ("ellipsoid", (20, 40, 120))])
+def test_isotropic_mc_matches_quadrature(orc, kind, size):
+    # Monte Carlo draws of an isotropic orientation (cos theta uniform) give
+    # the same detector total as the exact orientation average
+    mc = W.params(kind=kind, size=size, orient_kind="isotropic", mode="mc")
+    qd = dict(mc, mode="quad", quad_n=40)
+    n = 200_000
+    det, w2, _ = orc.trace(mc, n, 9, nthreads=8, with_w2=True, with_count=True)
+    mean = det.sum() / n
+    sigma = math.sqrt(max(w2.sum() / n - mean**2, 0.0) / n)
+    n_q = 4000
+    dq = orc.trace(qd, n_q, 9, nthreads=8)
+    # the quadrature tracer still samples lambda and t: its own MC error is
+    # much smaller (no orientation variance); compare within both errors
+    pix, wq, _ = orc.trace_debug(qd, n_q, 9)
+    sq = wq.std() / math.sqrt(n_q)
+    assert abs(mean - dq.sum() / n_q) < 4 * math.hypot(sigma, sq)
+
+
+def test_paper_uniform_angles_overweight_poles(orc):
+    # the literal uniform-angle rule (theta ~ U[0, pi]) is not isotropic:
+    # it puts the C axis nearer the poles (z, the beam) than cos-uniform
+    iso = W.params(kind="cylinder", size=(20, 400, 0), orient_kind="isotropic")
+    lit = dict(iso, orient_kind="uniform_angles")
+    n = 100_000
+    a = orc.trace(iso, n, 4, nthreads=8).sum()
+    b = orc.trace(lit, n, 4, nthreads=8).sum()
+    # rods along the beam scatter their full sinc-free cross-section into the
+    # cone; the literal rule therefore gives the larger total
+    assert b > a * 1.05
+
+
+def test_chunked_equals_whole(orc):
+    p = W.workload("coreshell_py")["params"]
+    p = dict(p, nx=64, ny=64)
+    whole = orc.trace(p, 30000, 2, nthreads=3)
+    parts = orc.trace(p, 10000, 2, first=0) + orc.trace(p, 20000, 2, first=10000)
+    assert np.allclose(whole, parts, rtol=1e-12, atol=0)
+
+
+def test_experiment_id_changes_stream(orc):
+    p = W.workload("tiny_sphere")["params"]
+    a = orc.trace_debug(p, 100, 1, exp_id=0)[1]
+    b = orc.trace_debug(p, 100, 1, exp_id=1)[1]
+    assert not np.allclose(a, b)
