@@ -1,0 +1,224 @@
+/*
+ * sans.h -- C ABI of libsans, the MI355X (gfx950) small-angle neutron
+ * scattering sample tracer.
+ *
+ * The library traces independent neutrons through a small-angle scattering
+ * sample and tallies them on an area detector, one neutron per GPU lane.
+ * The physics is that of arXiv 2501.06054 ("Small Angle Neutron Scattering in
+ * McStas: optimization for high throughput virtual experiments"):
+ *   - per scattering event the intensity is n (drho)^2 V^2 P(Q) S(Q), Eq. (3),
+ *     with n = phi/<V>, built from the particle amplitude of Eq. (1) (|A|^2,
+ *     Eqs. (2) and (4));
+ *   - isotropic amplitudes depend on |Q| (Eq. (5)); particles without a
+ *     symmetry axis on the projections Q_A, Q_B, Q_C (Eq. (6)); particles with
+ *     one symmetry axis on Q_AB and Q_C (Eq. (7)); the cylinder amplitude is
+ *     Eq. (9) (read with the sinc factor on the axis projection);
+ *   - size (polydispersity) and orientation are drawn anew at every
+ *     scattering event (Methods, "Polydispersity and orientational
+ *     distributions");
+ *   - neutrons are independent and the detector is summed with atomic
+ *     updates (Methods, "Acceleration schemes").
+ * Instrument, weight, random numbers (Philox4x32-10), tables and the
+ * hard-sphere Percus-Yevick S(Q) are the library's own readings where the
+ * paper is silent; they are documented field by field below.
+ *
+ * Conventions for every entry point
+ *   - Return value: SANS_OK (0) or a negative SANS_E_* status; the text of
+ *     the last error of the calling thread is returned by sans_last_error().
+ *     No entry point throws, aborts or exits.
+ *   - Pointers documented as "device" are HIP device pointers (for instance
+ *     the data of a PyTorch CUDA/HIP tensor); they are owned by the caller and
+ *     must stay valid until the work queued on the stream has finished.  The
+ *     library never frees caller memory.  Pointers documented as "host" are
+ *     read (or written) before the call returns.
+ *   - stream is a hipStream_t (NULL: the default stream).  All GPU work is
+ *     queued asynchronously on it; nothing synchronises the device.
+ *   - Detectors are FP64, row-major [ny][nx], pixel p = iy*nx + ix.
+ *   - A neutron count of 0 is a successful no-op (an overwritten detector is
+ *     still cleared).
+ *   - The random stream of neutron i of experiment e is a pure function of
+ *     (seed, e, i): results do not depend on the launch shape, the chunking of
+ *     [first, first+n) or the tally strategy, apart from the order of FP64
+ *     summation.
+ */
+#ifndef SANS_H
+#define SANS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SANS_ABI_VERSION 1u
+
+/* Status codes. */
+#define SANS_OK 0
+#define SANS_E_INVALID_ARG (-1) /* null pointer, bad size, value out of range  */
+#define SANS_E_UNSUPPORTED (-2) /* mode/model/option combination not provided  */
+#define SANS_E_NOMEM (-3)       /* device or host allocation failed            */
+#define SANS_E_HIP (-4)         /* a HIP runtime call failed (see last error)  */
+#define SANS_E_DOMAIN (-5)      /* inputs outside a model's valid domain        */
+
+/* Particle models (Tables I and II of the paper; this library provides five). */
+typedef enum {
+    SANS_SPHERE = 0,           /* size[0] = R                                   */
+    SANS_CORE_SHELL_SPHERE = 1,/* size[0] = core R, shell = thickness            */
+    SANS_CYLINDER = 2,         /* size[0] = R, size[1] = L; axis = particle C    */
+    SANS_ELLIPSOID = 3,        /* semi-axes size[0..2] along particle A, B, C    */
+    SANS_PARALLELEPIPED = 4    /* edges size[0..2] along particle A, B, C        */
+} sans_kind;
+
+/* How the particle size and orientation enter the weight. */
+typedef enum {
+    SANS_MODE_MC = 0,        /* drawn per event (the paper's method)             */
+    SANS_MODE_QUAD = 1,      /* exact Gauss-Legendre average per event           */
+    SANS_MODE_SURROGATE = 2  /* learned average (needs an attached network)      */
+} sans_mode;
+
+/* Orientation distribution of anisotropic particles.  The particle axes are
+ * A = R x, B = R y, C = R z with R = Rz(phi) Ry(theta) Rz(Psi): theta and phi
+ * place the C axis, Psi turns the particle about it (the angles that come
+ * with Eq. (6)). */
+typedef enum {
+    SANS_ORIENT_FIXED = 0,          /* angles = orient_mean                      */
+    SANS_ORIENT_GAUSSIAN = 1,       /* angle_k = mean_k + sigma_k N(0,1)         */
+    SANS_ORIENT_ISOTROPIC = 2,      /* cos theta ~ U[-1,1], phi, Psi ~ U[0,2pi]  */
+    SANS_ORIENT_UNIFORM_ANGLES = 3  /* the paper's literal rule: theta ~ U[0,pi],
+                                       phi, Psi ~ U[0,2pi] (not isotropic)       */
+} sans_orient;
+
+/* Tally strategies (all give the same detector up to FP64 summation order). */
+typedef enum {
+    SANS_TALLY_AUTO = 0,   /* library choice (tuned)                            */
+    SANS_TALLY_GLOBAL = 1, /* one FP64 global atomic per detected neutron        */
+    SANS_TALLY_LDS = 2,    /* workgroup-private FP64 histogram in LDS, flushed   */
+    SANS_TALLY_XCD = 3     /* one detector replica per XCD, summed at the end     */
+} sans_tally;
+
+/* Flags. */
+#define SANS_ACCUMULATE 1u /* add to the detector instead of overwriting it     */
+
+/* All parameters of one virtual experiment.  Plain data; set abi_version to
+ * SANS_ABI_VERSION.  Geometry in metres, wavelength and sizes in Angstrom,
+ * scattering-length densities in 1/Angstrom^2, angles in radians.
+ *
+ * Instrument (a synthetic stand-in for the paper's KWS-1 model): a neutron
+ * leaves a uniform point of the src_w x src_h source at z = src_z and flies to
+ * a uniform point of the slit_w x slit_h slit at z = slit_z; its wavelength is
+ * uniform in lambda0 (1 +- dlambda_rel).  The sample is the slab
+ * |x| < sample_w/2, |y| < sample_h/2, |z| < sample_d/2; the scattering point is
+ * uniform along the path inside it (length l).  The scattered direction is
+ * uniform in solid angle inside the cone of half-angle cone_alpha about the
+ * incident direction.  The detector is the plane z = det_z, |x| < det_w/2,
+ * |y| < det_h/2, with nx x ny pixels.
+ *
+ * Weight of a detected neutron (forced single scattering, unit initial weight):
+ *   w = l[A] * dOmega * (phi / <V>) * F^2 * S(q),
+ * dOmega = 2 pi (1 - cos cone_alpha), F the particle amplitude in Angstrom
+ * (F^2 = (drho V)^2 P), <V> the number-averaged particle volume, S the
+ * Percus-Yevick hard-sphere structure factor of radius sq_radius and volume
+ * fraction sq_phi (S = 1 when sq_phi = 0; fixed radius, decoupled from the
+ * drawn size).  Misses of the sample or the detector are not tallied. */
+typedef struct {
+    uint32_t abi_version;
+    int32_t kind;            /* sans_kind                                      */
+    int32_t mode;            /* sans_mode                                      */
+    int32_t orient_kind;     /* sans_orient                                    */
+    double size[3];
+    double shell;
+    double sld[3];           /* particle (core), shell, solvent                */
+    double phi;              /* particle volume fraction (number density phi/<V>) */
+    double sq_phi;           /* hard-sphere volume fraction, in [0, 0.6)       */
+    double sq_radius;        /* hard-sphere radius                             */
+    double poly;             /* Schulz relative width sigma/mean of the size draw
+                                y (mean 1); 0 = monodisperse                   */
+    int32_t poly_mask;       /* bit k set: size[k] is multiplied by y (the core-
+                                shell shell never is)                          */
+    int32_t table_size;      /* knots of the inverse-CDF tables (64..8192)     */
+    double orient_mean[3];   /* theta, phi, Psi                                */
+    double orient_sigma[3];  /* Gaussian spreads (SANS_ORIENT_GAUSSIAN)        */
+    double src_w, src_h, src_z;
+    double slit_w, slit_h, slit_z;
+    double lambda0, dlambda_rel, cone_alpha;
+    double sample_w, sample_h, sample_d;
+    double det_w, det_h, det_z;
+    int32_t nx, ny;
+    int32_t quad_n;          /* Gauss-Legendre order of SANS_MODE_QUAD (<= 256) */
+    int32_t tally;           /* sans_tally                                     */
+} sans_params;
+
+typedef struct sans_model_s* sans_model_t;
+
+/* Validates p, builds the inverse-CDF tables (standard normal and Schulz
+ * quantiles at (k + 1/2)/M, FP64 on the host, stored as FP32 on the device)
+ * and the model constants.  *out receives an opaque handle owning its device
+ * buffers.  Errors: SANS_E_INVALID_ARG (null pointers, wrong abi_version, a
+ * size <= 0, negative widths or spreads, phi or sq_phi outside [0, 1) / [0,
+ * 0.6), nx*ny outside 1..2^26), SANS_E_UNSUPPORTED (unknown kind/mode/orient,
+ * QUAD with Gaussian or uniform-angle orientation), SANS_E_NOMEM, SANS_E_HIP. */
+int sans_model_create(const sans_params* p, sans_model_t* out);
+
+/* Frees the handle and its device buffers (after synchronising its streams'
+ * pending use is the caller's duty).  NULL is accepted. */
+int sans_model_destroy(sans_model_t m);
+
+/* Traces neutrons 0 .. n_neutrons-1 of experiment 0 with the given seed and
+ * overwrites detector_out (device, FP64 [ny][nx]).  params: NULL to use the
+ * handle's parameters, otherwise new parameters that replace them for this and
+ * later calls (validated as in sans_model_create; the kind may change).  This
+ * is the paper's per-neutron Monte Carlo (Methods; Eq. (3)). */
+int sans_trace(sans_model_t m, uint64_t n_neutrons, uint64_t seed, const sans_params* params,
+               double* detector_out, void* stream);
+
+/* As sans_trace for neutrons first .. first+n-1 of experiment exp_id.  flags:
+ * SANS_ACCUMULATE adds to det (chunked or sharded runs).  det_w2 (sum of w^2)
+ * and det_count (hits, uint64) are optional device outputs (NULL = none) and
+ * follow the same overwrite/accumulate rule. */
+int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
+                  uint32_t flags, double* det, double* det_w2, uint64_t* det_count,
+                  void* stream);
+
+/* Per-neutron outputs for neutrons first .. first+n-1, computed by the same
+ * device code as the tally kernels: pixel (device int32, -1 = not tallied),
+ * w (device float, 0 when not tallied) and q = |Q| (device float, 0 when the
+ * sample is missed).  Any output may be NULL. */
+int sans_debug_trace(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed,
+                     uint32_t exp_id, int32_t* pixel, float* w, float* q, void* stream);
+
+/* Raw Philox4x32-10 words (Salmon et al., SC'11) of the neutron streams:
+ * out (device uint32 [n][n_blocks][4]) receives block b of neutron first+j,
+ * counter (lo i, hi i, b, exp_id), key (lo seed, hi seed). */
+int sans_debug_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t n_blocks,
+                      uint32_t exp_id, uint32_t* out, void* stream);
+
+/* Copies the handle's FP32 table knots to host memory: which = 0 standard
+ * normal, 1 Schulz.  out (host float [n]) with n = table_size.
+ * SANS_E_UNSUPPORTED if the handle has no such table. */
+int sans_debug_table(sans_model_t m, int32_t which, float* out, int32_t n);
+
+/* Evaluates, on the device, the weight factor F^2 that replaces the drawn
+ * size and orientation in SANS_MODE_QUAD: the Schulz size average and, for
+ * isotropic orientation, the orientation average of F^2 by Gauss-Legendre
+ * quadrature at q (device float [n]) -> out (device float [n]).  Fixed
+ * orientation takes qvec (device float [n][3], may be NULL for isotropic
+ * models). */
+int sans_pq_avg(sans_model_t m, const float* q, const float* qvec, int64_t n, float* out,
+                void* stream);
+
+/* Host-side constants of the handle, for tests: out[0] = <V>, out[1] = the
+ * per-metre weight scale 1e10 * dOmega * phi / <V>, out[2] = 1 - cos alpha. */
+int sans_model_constants(sans_model_t m, double* out3);
+
+/* sizeof(sans_params) as compiled into the library (binding layout check). */
+uint32_t sans_abi_params_size(void);
+
+/* Text of a status code, and of the last error of the calling thread. */
+const char* sans_status_string(int status);
+const char* sans_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SANS_H */

@@ -1,0 +1,748 @@
+// sans_lib.hip -- kernels and C ABI of libsans (gfx950).
+//
+// Kernels
+//   k_trace<KIND, MODE, TALLY>  the hot path: one neutron per lane, grid-stride
+//                               over the neutron range, tally into the detector
+//   k_debug<KIND, MODE>         the same per-neutron code, writing (pixel, w, q)
+//   k_philox                    raw Philox words for stream tests
+//   k_fill, k_sum_replicas      detector clearing / XCD replica reduction
+//   k_pq_avg<KIND>              the exact average <F^2>(q) alone
+// The model switch is a template parameter: a wavefront never diverges on it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sans.h"
+#include "sans_device.hpp"
+#include "sans_host_math.hpp"
+
+using namespace sans;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kXcds = 8;
+constexpr size_t kLdsMax = 160 * 1024;
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg)
+{
+    g_last_error = msg;
+    return status;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(SANS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+// ------------------------------------------------------------------ kernels
+
+// Stage a float array into LDS with all threads of the block.
+__device__ __forceinline__ void stage(float* dst, const float* src, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// Dynamic LDS: [hist (LDS tally only)] [size table] [normal table] [quad nodes]
+struct LdsLayout {
+    int hist_doubles, tab_size_off, tab_norm_off, quad_off, total_floats;
+};
+
+template <int KIND, int MODE, int TALLY>
+__global__ __launch_bounds__(kBlock) void k_trace(const TraceArgs a, LdsLayout lay, double* det,
+                                                  double* det_w2, unsigned long long* det_cnt,
+                                                  double* replicas)
+{
+    extern __shared__ double lds_d[];
+    float* lds_f = reinterpret_cast<float*>(lds_d + lay.hist_doubles);
+    float* tsize = lds_f + lay.tab_size_off;
+    float* tnorm = lds_f + lay.tab_norm_off;
+    float* lq = lds_f + lay.quad_off;
+    if (a.tab_size) stage(tsize, a.tab_size, a.M);
+    if (a.tab_norm) stage(tnorm, a.tab_norm, a.M);
+    if constexpr (MODE == 1) {
+        stage(lq, a.quad_mu, a.quad_n);
+        stage(lq + a.quad_n, a.quad_wmu, a.quad_n);
+        stage(lq + 2 * a.quad_n, a.quad_cb, a.quad_n);
+        stage(lq + 3 * a.quad_n, a.quad_sb, a.quad_n);
+        stage(lq + 4 * a.quad_n, a.quad_wb, a.quad_n);
+        stage(lq + 5 * a.quad_n, a.quad_y, a.quad_ny);
+        stage(lq + 5 * a.quad_n + a.quad_ny, a.quad_wy, a.quad_ny);
+    }
+    const int npix = a.nx * a.ny;
+    if constexpr (TALLY == SANS_TALLY_LDS) {
+        for (int i = threadIdx.x; i < npix; i += blockDim.x) lds_d[i] = 0.0;
+    }
+    __syncthreads();
+
+    double* target = det;
+    if constexpr (TALLY == SANS_TALLY_XCD) {
+        const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kXcds - 1);
+        target = replicas + (size_t)xcc * npix;
+    }
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += stride) {
+        const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, tsize, tnorm, lq);
+        if (ev.pixel >= 0) {
+            const double w = (double)ev.w;
+            if constexpr (TALLY == SANS_TALLY_LDS) {
+                __hip_atomic_fetch_add(lds_d + ev.pixel, w, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+                __hip_atomic_fetch_add(target + ev.pixel, w, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (det_w2)
+                __hip_atomic_fetch_add(det_w2 + ev.pixel, w * w, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            if (det_cnt)
+                __hip_atomic_fetch_add(det_cnt + ev.pixel, 1ull, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if constexpr (TALLY == SANS_TALLY_LDS) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < npix; i += blockDim.x) {
+            const double v = lds_d[i];
+            if (v != 0.0)
+                __hip_atomic_fetch_add(det + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <int KIND, int MODE>
+__global__ __launch_bounds__(kBlock) void k_debug(const TraceArgs a, LdsLayout lay, int32_t* pixel,
+                                                  float* w, float* q)
+{
+    extern __shared__ double lds_d[];
+    float* lds_f = reinterpret_cast<float*>(lds_d);
+    float* tsize = lds_f + lay.tab_size_off;
+    float* tnorm = lds_f + lay.tab_norm_off;
+    float* lq = lds_f + lay.quad_off;
+    if (a.tab_size) stage(tsize, a.tab_size, a.M);
+    if (a.tab_norm) stage(tnorm, a.tab_norm, a.M);
+    if constexpr (MODE == 1) {
+        stage(lq, a.quad_mu, a.quad_n);
+        stage(lq + a.quad_n, a.quad_wmu, a.quad_n);
+        stage(lq + 2 * a.quad_n, a.quad_cb, a.quad_n);
+        stage(lq + 3 * a.quad_n, a.quad_sb, a.quad_n);
+        stage(lq + 4 * a.quad_n, a.quad_wb, a.quad_n);
+        stage(lq + 5 * a.quad_n, a.quad_y, a.quad_ny);
+        stage(lq + 5 * a.quad_n + a.quad_ny, a.quad_wy, a.quad_ny);
+    }
+    __syncthreads();
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
+    const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, tsize, tnorm, lq);
+    if (pixel) pixel[j] = ev.pixel;
+    if (w) w[j] = ev.w;
+    if (q) q[j] = ev.q;
+}
+
+__global__ void k_philox(uint32_t seed_lo, uint32_t seed_hi, uint64_t first, uint64_t n,
+                         uint32_t nblocks, uint32_t exp_id, uint32_t* out)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint64_t i = first + j;
+    for (uint32_t b = 0; b < nblocks; ++b) {
+        const U4 r = philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), b, exp_id, seed_lo, seed_hi);
+        uint32_t* o = out + (j * nblocks + b) * 4;
+        o[0] = r.x;
+        o[1] = r.y;
+        o[2] = r.z;
+        o[3] = r.w;
+    }
+}
+
+__global__ void k_fill(double* p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// det[i] (+)= sum over the XCD replicas, which are cleared for the next run.
+__global__ void k_sum_replicas(double* det, double* rep, int npix, int accumulate)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix) return;
+    double s = accumulate ? det[i] : 0.0;
+#pragma unroll
+    for (int x = 0; x < kXcds; ++x) {
+        s += rep[(size_t)x * npix + i];
+        rep[(size_t)x * npix + i] = 0.0;
+    }
+    det[i] = s;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_pq_avg(const TraceArgs a, LdsLayout lay, const float* q,
+                                                   const float* qvec, int64_t n, float* out)
+{
+    extern __shared__ double lds_d[];
+    float* lq = reinterpret_cast<float*>(lds_d) + lay.quad_off;
+    stage(lq, a.quad_mu, a.quad_n);
+    stage(lq + a.quad_n, a.quad_wmu, a.quad_n);
+    stage(lq + 2 * a.quad_n, a.quad_cb, a.quad_n);
+    stage(lq + 3 * a.quad_n, a.quad_sb, a.quad_n);
+    stage(lq + 4 * a.quad_n, a.quad_wb, a.quad_n);
+    stage(lq + 5 * a.quad_n, a.quad_y, a.quad_ny);
+    stage(lq + 5 * a.quad_n + a.quad_ny, a.quad_wy, a.quad_ny);
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    float qv[3] = {0.0f, 0.0f, 0.0f};
+    if (qvec) {
+        qv[0] = qvec[3 * j];
+        qv[1] = qvec[3 * j + 1];
+        qv[2] = qvec[3 * j + 2];
+    }
+    out[j] = quad_average<KIND>(a, lq, q[j], qv);
+}
+
+// ------------------------------------------------------------------ dispatch tables
+using TraceFn = void (*)(const TraceArgs, LdsLayout, double*, double*, unsigned long long*, double*);
+using DebugFn = void (*)(const TraceArgs, LdsLayout, int32_t*, float*, float*);
+using PqFn = void (*)(const TraceArgs, LdsLayout, const float*, const float*, int64_t, float*);
+
+template <int K, int M>
+TraceFn trace_fn(int tally)
+{
+    return tally == SANS_TALLY_LDS ? (TraceFn)k_trace<K, M, SANS_TALLY_LDS>
+         : tally == SANS_TALLY_XCD ? (TraceFn)k_trace<K, M, SANS_TALLY_XCD>
+                                   : (TraceFn)k_trace<K, M, SANS_TALLY_GLOBAL>;
+}
+
+TraceFn pick_trace(int kind, int mode, int tally)
+{
+#define SANS_CASE(K)                                                                       \
+    case K:                                                                                \
+        return mode == 0 ? trace_fn<K, 0>(tally) : trace_fn<K, 1>(tally);
+    switch (kind) {
+        SANS_CASE(0)
+        SANS_CASE(1)
+        SANS_CASE(2)
+        SANS_CASE(3)
+        SANS_CASE(4)
+    }
+#undef SANS_CASE
+    return nullptr;
+}
+
+DebugFn pick_debug(int kind, int mode)
+{
+#define SANS_CASE(K)                                                                       \
+    case K:                                                                                \
+        return mode == 0 ? (DebugFn)k_debug<K, 0> : (DebugFn)k_debug<K, 1>;
+    switch (kind) {
+        SANS_CASE(0)
+        SANS_CASE(1)
+        SANS_CASE(2)
+        SANS_CASE(3)
+        SANS_CASE(4)
+    }
+#undef SANS_CASE
+    return nullptr;
+}
+
+PqFn pick_pq(int kind)
+{
+    switch (kind) {
+    case 0: return k_pq_avg<0>;
+    case 1: return k_pq_avg<1>;
+    case 2: return k_pq_avg<2>;
+    case 3: return k_pq_avg<3>;
+    case 4: return k_pq_avg<4>;
+    }
+    return nullptr;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ model handle
+struct sans_model_s {
+    sans_params p;
+    TraceArgs args;            // constants; per-call fields are filled at launch
+    double mean_v = 0.0, wscale = 0.0, omc = 0.0;
+    std::vector<float> h_tab_size, h_tab_norm, h_quad;
+    float* d_tab_size = nullptr;
+    float* d_tab_norm = nullptr;
+    float* d_quad = nullptr;
+    double* d_replicas = nullptr;
+    size_t replica_pix = 0;
+    int device = 0;
+    int num_cu = 256;
+};
+
+namespace {
+
+bool finite(double x) { return std::isfinite(x); }
+
+int validate(const sans_params* p)
+{
+    if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
+    if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
+    if (p->kind < 0 || p->kind > 4) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
+    if (p->mode == SANS_MODE_SURROGATE)
+        return fail(SANS_E_UNSUPPORTED, "surrogate mode needs an attached network");
+    if (p->orient_kind < 0 || p->orient_kind > 3) return fail(SANS_E_UNSUPPORTED, "unknown orientation kind");
+    if (p->tally < 0 || p->tally > 3) return fail(SANS_E_UNSUPPORTED, "unknown tally strategy");
+    const int nsize = p->kind <= 1 ? 1 : (p->kind == 2 ? 2 : 3);
+    for (int k = 0; k < nsize; ++k)
+        if (!(p->size[k] > 0.0) || !finite(p->size[k])) return fail(SANS_E_INVALID_ARG, "size must be > 0");
+    if (p->kind == 1 && !(p->shell >= 0.0 && finite(p->shell)))
+        return fail(SANS_E_INVALID_ARG, "shell must be >= 0");
+    for (int k = 0; k < 3; ++k)
+        if (!finite(p->sld[k])) return fail(SANS_E_INVALID_ARG, "sld must be finite");
+    if (!(p->phi >= 0.0 && p->phi < 1.0)) return fail(SANS_E_INVALID_ARG, "phi must be in [0, 1)");
+    if (!(p->sq_phi >= 0.0 && p->sq_phi < 0.6)) return fail(SANS_E_INVALID_ARG, "sq_phi must be in [0, 0.6)");
+    if (p->sq_phi > 0.0 && !(p->sq_radius > 0.0)) return fail(SANS_E_INVALID_ARG, "sq_radius must be > 0");
+    if (!(p->poly >= 0.0 && p->poly <= 1.0)) return fail(SANS_E_INVALID_ARG, "poly must be in [0, 1]");
+    if (p->poly > 0.0 && p->poly < 1e-4) return fail(SANS_E_INVALID_ARG, "poly must be 0 or >= 1e-4");
+    if (p->poly_mask < 0 || p->poly_mask > 7) return fail(SANS_E_INVALID_ARG, "poly_mask must be in 0..7");
+    if (p->table_size < 64 || p->table_size > 8192)
+        return fail(SANS_E_INVALID_ARG, "table_size must be in 64..8192");
+    for (int k = 0; k < 3; ++k) {
+        if (!finite(p->orient_mean[k])) return fail(SANS_E_INVALID_ARG, "orient_mean must be finite");
+        if (!(p->orient_sigma[k] >= 0.0) || !finite(p->orient_sigma[k]))
+            return fail(SANS_E_INVALID_ARG, "orient_sigma must be >= 0");
+    }
+    const double pos[] = {p->src_w, p->src_h, p->slit_w, p->slit_h, p->lambda0, p->cone_alpha,
+                          p->sample_w, p->sample_h, p->sample_d, p->det_w, p->det_h};
+    for (double v : pos)
+        if (!(v >= 0.0) || !finite(v)) return fail(SANS_E_INVALID_ARG, "instrument sizes must be >= 0");
+    if (!(p->lambda0 > 0.0) || !(p->det_w > 0.0) || !(p->det_h > 0.0))
+        return fail(SANS_E_INVALID_ARG, "lambda0, det_w, det_h must be > 0");
+    if (!(p->cone_alpha > 0.0 && p->cone_alpha < 1.5))
+        return fail(SANS_E_INVALID_ARG, "cone_alpha must be in (0, 1.5)");
+    if (!(p->dlambda_rel >= 0.0 && p->dlambda_rel < 1.0))
+        return fail(SANS_E_INVALID_ARG, "dlambda_rel must be in [0, 1)");
+    if (!finite(p->src_z) || !finite(p->slit_z) || !finite(p->det_z) || !(p->slit_z > p->src_z))
+        return fail(SANS_E_INVALID_ARG, "need src_z < slit_z (finite)");
+    if (p->nx < 1 || p->ny < 1 || (int64_t)p->nx * p->ny > (1 << 26))
+        return fail(SANS_E_INVALID_ARG, "nx*ny must be in 1..2^26");
+    if (p->mode == SANS_MODE_QUAD) {
+        if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
+        if (p->kind >= 2 && p->orient_kind != SANS_ORIENT_FIXED && p->orient_kind != SANS_ORIENT_ISOTROPIC)
+            return fail(SANS_E_UNSUPPORTED, "quadrature mode averages fixed or isotropic orientations only");
+    }
+    return SANS_OK;
+}
+
+// Fills the model's constants and (re)builds tables when needed.
+int configure(sans_model_s* m, const sans_params* p)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    const sans_params old = m->p;
+    const bool first = (m->d_tab_norm == nullptr && m->d_tab_size == nullptr && m->d_quad == nullptr
+                        && m->args.M == 0);
+    m->p = *p;
+    TraceArgs& a = m->args;
+    std::memset(&a, 0, sizeof(a));
+    a.src_w = p->src_w;
+    a.src_h = p->src_h;
+    a.src_z = p->src_z;
+    a.slit_w = p->slit_w;
+    a.slit_h = p->slit_h;
+    a.slit_z = p->slit_z;
+    a.lambda0 = p->lambda0;
+    a.lambda_span = p->lambda0 * p->dlambda_rel;
+    a.half_x = 0.5 * p->sample_w;
+    a.half_y = 0.5 * p->sample_h;
+    a.half_z = 0.5 * p->sample_d;
+    const double sh = std::sin(0.5 * p->cone_alpha);
+    m->omc = 2.0 * sh * sh;
+    a.omc = m->omc;
+    a.det_z = p->det_z;
+    a.det_hw = 0.5 * p->det_w;
+    a.det_hh = 0.5 * p->det_h;
+    a.inv_px = p->nx / p->det_w;
+    a.inv_py = p->ny / p->det_h;
+    a.nx = p->nx;
+    a.ny = p->ny;
+    m->mean_v = host::mean_volume(p->kind, p->size, p->shell, p->poly, p->poly_mask);
+    const double dOmega = 2.0 * 3.141592653589793 * m->omc;
+    m->wscale = 1e10 * dOmega * p->phi / m->mean_v;
+    a.wscale = m->wscale;
+    for (int k = 0; k < 3; ++k) {
+        a.size[k] = (float)p->size[k];
+        a.ang_mean[k] = (float)p->orient_mean[k];
+        a.ang_sigma[k] = (float)p->orient_sigma[k];
+    }
+    a.shell = (float)p->shell;
+    a.contrast = (float)(p->sld[0] - p->sld[2]);
+    a.cs_core = (float)(p->sld[0] - p->sld[1]);
+    a.cs_shell = (float)(p->sld[1] - p->sld[2]);
+    a.poly_on = p->poly > 0.0;
+    a.poly_mask = p->poly_mask;
+    a.orient_kind = p->orient_kind;
+    const bool aniso = p->kind >= 2;
+    a.third_block = p->mode == SANS_MODE_MC && (a.poly_on || (aniso && p->orient_kind != 0));
+    a.sq_on = p->sq_phi > 0.0;
+    if (a.sq_on) {
+        double c[kPySeriesTerms], abg[3];
+        host::py_series(p->sq_phi, kPySeriesTerms, c, abg);
+        for (int k = 0; k < kPySeriesTerms; ++k) a.py_c[k] = (float)c[k];
+        a.py_alpha = (float)abg[0];
+        a.py_beta = (float)abg[1];
+        a.py_gamma = (float)abg[2];
+        a.sq_2r = (float)(2.0 * p->sq_radius);
+        a.sq_24phi = (float)(24.0 * p->sq_phi);
+    }
+    a.M = p->table_size;
+
+    // tables
+    const bool need_size = p->mode == SANS_MODE_MC && a.poly_on;
+    const bool need_norm = p->mode == SANS_MODE_MC && aniso && p->orient_kind == SANS_ORIENT_GAUSSIAN;
+    const bool size_same = !first && old.table_size == p->table_size && old.poly == p->poly
+                           && !m->h_tab_size.empty();
+    const bool norm_same = !first && old.table_size == p->table_size && !m->h_tab_norm.empty();
+    if (need_size) {
+        if (!size_same) {
+            std::vector<double> t(p->table_size);
+            host::schulz_table(p->poly, p->table_size, t.data());
+            m->h_tab_size.assign(t.begin(), t.end());
+            if (m->d_tab_size) HIP_TRY(hipFree(m->d_tab_size));
+            m->d_tab_size = nullptr;
+            HIP_TRY(hipMalloc(&m->d_tab_size, sizeof(float) * p->table_size));
+            HIP_TRY(hipMemcpy(m->d_tab_size, m->h_tab_size.data(), sizeof(float) * p->table_size,
+                              hipMemcpyHostToDevice));
+        }
+        a.tab_size = m->d_tab_size;
+    }
+    if (need_norm) {
+        if (!norm_same) {
+            m->h_tab_norm.resize(p->table_size);
+            for (int k = 0; k < p->table_size; ++k)
+                m->h_tab_norm[k] = (float)host::normal_quantile((k + 0.5) / p->table_size);
+            if (m->d_tab_norm) HIP_TRY(hipFree(m->d_tab_norm));
+            m->d_tab_norm = nullptr;
+            HIP_TRY(hipMalloc(&m->d_tab_norm, sizeof(float) * p->table_size));
+            HIP_TRY(hipMemcpy(m->d_tab_norm, m->h_tab_norm.data(), sizeof(float) * p->table_size,
+                              hipMemcpyHostToDevice));
+        }
+        a.tab_norm = m->d_tab_norm;
+    }
+
+    // quadrature nodes: mu in [0, 1], beta in [0, pi/2], size y in
+    // [max(0, 1 - 6p), 1 + 8p] with Schulz weights normalised to sum 1
+    if (p->mode == SANS_MODE_QUAD) {
+        const int n = p->quad_n;
+        std::vector<double> gx(n), gw(n);
+        host::gauss_legendre(n, gx.data(), gw.data());
+        int ny = 1;
+        std::vector<double> ys(1, 1.0), wy(1, 1.0);
+        if (a.poly_on) {
+            ny = n;
+            ys.assign(n, 0.0);
+            wy.assign(n, 0.0);
+            const double lo = std::max(0.0, 1.0 - 6.0 * p->poly), hi = 1.0 + 8.0 * p->poly;
+            const double aa = 1.0 / (p->poly * p->poly);
+            const double lnorm = aa * std::log(aa) - std::lgamma(aa);
+            double tot = 0.0;
+            for (int j = 0; j < n; ++j) {
+                ys[j] = lo + 0.5 * (hi - lo) * (gx[j] + 1.0);
+                const double y = ys[j];
+                const double pdf = y > 0.0 ? std::exp(lnorm + (aa - 1.0) * std::log(y) - aa * y) : 0.0;
+                wy[j] = gw[j] * pdf;
+                tot += wy[j];
+            }
+            for (int j = 0; j < n; ++j) wy[j] /= tot;
+        }
+        int dims = 0;
+        if (aniso && p->orient_kind == SANS_ORIENT_ISOTROPIC) {
+            const bool spheroid = p->kind == 3 && p->size[0] == p->size[1]
+                                  && ((p->poly_mask & 1) != 0) == ((p->poly_mask & 2) != 0);
+            dims = (p->kind == 2 || spheroid) ? 1 : 2;
+        }
+        a.quad_n = n;
+        a.quad_ny = ny;
+        a.quad_dims = dims;
+        m->h_quad.assign(5 * n + 2 * ny, 0.0f);
+        for (int i = 0; i < n; ++i) {
+            const double mu = 0.5 * (gx[i] + 1.0);
+            const double beta = 0.25 * 3.141592653589793 * (gx[i] + 1.0);
+            m->h_quad[i] = (float)mu;
+            m->h_quad[n + i] = (float)(0.5 * gw[i]);
+            m->h_quad[2 * n + i] = (float)std::cos(beta);
+            m->h_quad[3 * n + i] = (float)std::sin(beta);
+            m->h_quad[4 * n + i] = (float)(0.5 * gw[i]);
+        }
+        for (int j = 0; j < ny; ++j) {
+            m->h_quad[5 * n + j] = (float)ys[j];
+            m->h_quad[5 * n + ny + j] = (float)wy[j];
+        }
+        if (m->d_quad) HIP_TRY(hipFree(m->d_quad));
+        m->d_quad = nullptr;
+        HIP_TRY(hipMalloc(&m->d_quad, sizeof(float) * m->h_quad.size()));
+        HIP_TRY(hipMemcpy(m->d_quad, m->h_quad.data(), sizeof(float) * m->h_quad.size(),
+                          hipMemcpyHostToDevice));
+        a.quad_mu = m->d_quad;
+        a.quad_wmu = m->d_quad + n;
+        a.quad_cb = m->d_quad + 2 * n;
+        a.quad_sb = m->d_quad + 3 * n;
+        a.quad_wb = m->d_quad + 4 * n;
+        a.quad_y = m->d_quad + 5 * n;
+        a.quad_wy = m->d_quad + 5 * n + ny;
+    }
+    return SANS_OK;
+}
+
+LdsLayout layout(const sans_model_s* m, bool hist)
+{
+    LdsLayout l{};
+    const TraceArgs& a = m->args;
+    l.hist_doubles = hist ? a.nx * a.ny : 0;
+    int off = 0;
+    l.tab_size_off = off;
+    if (a.tab_size) off += a.M;
+    l.tab_norm_off = off;
+    if (a.tab_norm) off += a.M;
+    l.quad_off = off;
+    if (m->p.mode == SANS_MODE_QUAD) off += 5 * a.quad_n + 2 * a.quad_ny;
+    l.total_floats = off;
+    return l;
+}
+
+size_t lds_bytes(const LdsLayout& l) { return sizeof(double) * l.hist_doubles + sizeof(float) * l.total_floats; }
+
+int choose_tally(const sans_model_s* m)
+{
+    const int t = m->p.tally;
+    const LdsLayout l = layout(m, true);
+    const bool fits = lds_bytes(l) <= kLdsMax;
+    if (t == SANS_TALLY_LDS && !fits) return SANS_TALLY_GLOBAL;
+    if (t != SANS_TALLY_AUTO) return t;
+    return fits ? SANS_TALLY_LDS : SANS_TALLY_GLOBAL;
+}
+
+int launch_fill(double* p, size_t n, hipStream_t s)
+{
+    if (n == 0) return SANS_OK;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    HIP_TRY(hipGetLastError());
+    return SANS_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* sans_status_string(int status)
+{
+    switch (status) {
+    case SANS_OK: return "ok";
+    case SANS_E_INVALID_ARG: return "invalid argument";
+    case SANS_E_UNSUPPORTED: return "unsupported";
+    case SANS_E_NOMEM: return "out of memory";
+    case SANS_E_HIP: return "HIP runtime error";
+    case SANS_E_DOMAIN: return "outside the model domain";
+    }
+    return "unknown status";
+}
+
+const char* sans_last_error(void) { return g_last_error.c_str(); }
+
+uint32_t sans_abi_params_size(void) { return (uint32_t)sizeof(sans_params); }
+
+int sans_model_create(const sans_params* p, sans_model_t* out)
+{
+    if (!out) return fail(SANS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc) return rc;
+    sans_model_s* m = new (std::nothrow) sans_model_s();
+    if (!m) return fail(SANS_E_NOMEM, "host allocation failed");
+    std::memset(&m->args, 0, sizeof(m->args));
+    hipError_t e = hipGetDevice(&m->device);
+    if (e == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, m->device) == hipSuccess) m->num_cu = prop.multiProcessorCount;
+    } else {
+        delete m;
+        return fail(SANS_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    rc = configure(m, p);
+    if (rc) {
+        sans_model_destroy(m);
+        return rc;
+    }
+    *out = m;
+    return SANS_OK;
+}
+
+int sans_model_destroy(sans_model_t m)
+{
+    if (!m) return SANS_OK;
+    if (m->d_tab_size) (void)hipFree(m->d_tab_size);
+    if (m->d_tab_norm) (void)hipFree(m->d_tab_norm);
+    if (m->d_quad) (void)hipFree(m->d_quad);
+    if (m->d_replicas) (void)hipFree(m->d_replicas);
+    delete m;
+    return SANS_OK;
+}
+
+int sans_model_constants(sans_model_t m, double* out3)
+{
+    if (!m || !out3) return fail(SANS_E_INVALID_ARG, "NULL argument");
+    out3[0] = m->mean_v;
+    out3[1] = m->wscale;
+    out3[2] = m->omc;
+    return SANS_OK;
+}
+
+int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
+                  uint32_t flags, double* det, double* det_w2, uint64_t* det_count, void* stream)
+{
+    if (!m || !det) return fail(SANS_E_INVALID_ARG, "model or detector is NULL");
+    if (flags & ~SANS_ACCUMULATE) return fail(SANS_E_INVALID_ARG, "unknown flags");
+    if (n > 0 && first + n < first) return fail(SANS_E_INVALID_ARG, "neutron range overflows");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t npix = (size_t)m->p.nx * m->p.ny;
+    const bool acc = flags & SANS_ACCUMULATE;
+    if (!acc) {
+        int rc = launch_fill(det, npix, s);
+        if (rc) return rc;
+        if (det_w2 && (rc = launch_fill(det_w2, npix, s))) return rc;
+        if (det_count) {
+            hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s,
+                               (unsigned long long*)det_count, npix);
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    if (n == 0) return SANS_OK;
+    const int tally = choose_tally(m);
+    if (tally == SANS_TALLY_XCD && m->replica_pix != npix) {
+        if (m->d_replicas) HIP_TRY(hipFree(m->d_replicas));
+        m->d_replicas = nullptr;
+        m->replica_pix = 0;
+        hipError_t e = hipMalloc(&m->d_replicas, sizeof(double) * npix * kXcds);
+        if (e != hipSuccess) return fail(SANS_E_NOMEM, "replica allocation failed");
+        m->replica_pix = npix;
+        int rc = launch_fill(m->d_replicas, npix * kXcds, s);
+        if (rc) return rc;
+    }
+    TraceArgs a = m->args;
+    a.first = first;
+    a.n = n;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    a.exp_id = exp_id;
+    const LdsLayout lay = layout(m, tally == SANS_TALLY_LDS);
+    const size_t shmem = lds_bytes(lay);
+    TraceFn fn = pick_trace(m->p.kind, m->p.mode, tally);
+    if (!fn) return fail(SANS_E_UNSUPPORTED, "no kernel for this model");
+    if (shmem > 64 * 1024)
+        HIP_TRY(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+    // grid: enough waves to fill every CU; the kernel strides over the range
+    uint64_t blocks_needed = (n + kBlock - 1) / kBlock;
+    uint64_t max_blocks;
+    if (tally == SANS_TALLY_LDS) {
+        const int per_cu = std::max<int>(1, (int)(kLdsMax / std::max<size_t>(shmem, 1)));
+        max_blocks = (uint64_t)m->num_cu * std::min(per_cu, 8);
+    } else {
+        max_blocks = (uint64_t)m->num_cu * 8;
+    }
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(blocks_needed, max_blocks));
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), shmem, s, a, lay, det, det_w2,
+                       (unsigned long long*)det_count, m->d_replicas);
+    HIP_TRY(hipGetLastError());
+    if (tally == SANS_TALLY_XCD) {
+        hipLaunchKernelGGL(k_sum_replicas, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, det,
+                           m->d_replicas, (int)npix, 1);
+        HIP_TRY(hipGetLastError());
+    }
+    return SANS_OK;
+}
+
+int sans_trace(sans_model_t m, uint64_t n_neutrons, uint64_t seed, const sans_params* params,
+               double* detector_out, void* stream)
+{
+    if (!m) return fail(SANS_E_INVALID_ARG, "model is NULL");
+    if (params) {
+        int rc = configure(m, params);
+        if (rc) return rc;
+    }
+    return sans_trace_ex(m, 0, n_neutrons, seed, 0, 0, detector_out, nullptr, nullptr, stream);
+}
+
+int sans_debug_trace(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
+                     int32_t* pixel, float* w, float* q, void* stream)
+{
+    if (!m) return fail(SANS_E_INVALID_ARG, "model is NULL");
+    if (n == 0) return SANS_OK;
+    if (n > (1ull << 31)) return fail(SANS_E_INVALID_ARG, "debug range limited to 2^31 neutrons");
+    TraceArgs a = m->args;
+    a.first = first;
+    a.n = n;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    a.exp_id = exp_id;
+    const LdsLayout lay = layout(m, false);
+    DebugFn fn = pick_debug(m->p.kind, m->p.mode);
+    if (!fn) return fail(SANS_E_UNSUPPORTED, "no kernel for this model");
+    hipLaunchKernelGGL(fn, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), lds_bytes(lay),
+                       (hipStream_t)stream, a, lay, pixel, w, q);
+    HIP_TRY(hipGetLastError());
+    return SANS_OK;
+}
+
+int sans_debug_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t n_blocks, uint32_t exp_id,
+                      uint32_t* out, void* stream)
+{
+    if (!out) return fail(SANS_E_INVALID_ARG, "out is NULL");
+    if (n_blocks < 1 || n_blocks > 16) return fail(SANS_E_INVALID_ARG, "n_blocks must be in 1..16");
+    if (n == 0) return SANS_OK;
+    if (n > (1ull << 30)) return fail(SANS_E_INVALID_ARG, "n too large");
+    hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), first, n, n_blocks, exp_id, out);
+    HIP_TRY(hipGetLastError());
+    return SANS_OK;
+}
+
+int sans_debug_table(sans_model_t m, int32_t which, float* out, int32_t n)
+{
+    if (!m || !out) return fail(SANS_E_INVALID_ARG, "NULL argument");
+    const std::vector<float>& t = which == 0 ? m->h_tab_norm : m->h_tab_size;
+    if (which < 0 || which > 1 || t.empty()) return fail(SANS_E_UNSUPPORTED, "no such table");
+    if (n != (int32_t)t.size()) return fail(SANS_E_INVALID_ARG, "n must equal table_size");
+    std::memcpy(out, t.data(), sizeof(float) * n);
+    return SANS_OK;
+}
+
+int sans_pq_avg(sans_model_t m, const float* q, const float* qvec, int64_t n, float* out, void* stream)
+{
+    if (!m || !q || !out) return fail(SANS_E_INVALID_ARG, "NULL argument");
+    if (m->p.mode != SANS_MODE_QUAD) return fail(SANS_E_UNSUPPORTED, "model is not in quadrature mode");
+    if (n < 0) return fail(SANS_E_INVALID_ARG, "n < 0");
+    if (m->args.quad_dims == 0 && m->p.kind >= 2 && !qvec)
+        return fail(SANS_E_INVALID_ARG, "fixed orientation needs qvec");
+    if (n == 0) return SANS_OK;
+    const LdsLayout lay = layout(m, false);
+    hipLaunchKernelGGL(pick_pq(m->p.kind), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                       lds_bytes(lay), (hipStream_t)stream, m->args, lay, q, qvec, n, out);
+    HIP_TRY(hipGetLastError());
+    return SANS_OK;
+}
+
+}  // extern "C"

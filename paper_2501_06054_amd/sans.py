@@ -1,0 +1,247 @@
+"""Thin ctypes binding of libsans (see include/sans.h).
+
+Argument marshalling only: every step of the trace runs in the library's
+HIP kernels.  PyTorch supplies device memory and streams.  The names follow
+the C ABI one to one (sans_model_create, sans_trace, ...).  If the library is
+missing the import fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # loaded first so that libsans shares PyTorch's HIP runtime
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsans.so")
+
+SANS_ABI_VERSION = 1
+SANS_OK = 0
+SANS_E_INVALID_ARG = -1
+SANS_E_UNSUPPORTED = -2
+SANS_E_NOMEM = -3
+SANS_E_HIP = -4
+SANS_E_DOMAIN = -5
+SANS_ACCUMULATE = 1
+
+KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelepiped": 4}
+MODE = {"mc": 0, "quad": 1, "surrogate": 2}
+ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
+TALLY = {"auto": 0, "global": 1, "lds": 2, "xcd": 3}
+
+
+class SansError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class sans_params(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_uint32), ("kind", C.c_int32), ("mode", C.c_int32),
+        ("orient_kind", C.c_int32),
+        ("size", C.c_double * 3), ("shell", C.c_double), ("sld", C.c_double * 3),
+        ("phi", C.c_double), ("sq_phi", C.c_double), ("sq_radius", C.c_double),
+        ("poly", C.c_double), ("poly_mask", C.c_int32), ("table_size", C.c_int32),
+        ("orient_mean", C.c_double * 3), ("orient_sigma", C.c_double * 3),
+        ("src_w", C.c_double), ("src_h", C.c_double), ("src_z", C.c_double),
+        ("slit_w", C.c_double), ("slit_h", C.c_double), ("slit_z", C.c_double),
+        ("lambda0", C.c_double), ("dlambda_rel", C.c_double), ("cone_alpha", C.c_double),
+        ("sample_w", C.c_double), ("sample_h", C.c_double), ("sample_d", C.c_double),
+        ("det_w", C.c_double), ("det_h", C.c_double), ("det_z", C.c_double),
+        ("nx", C.c_int32), ("ny", C.c_int32), ("quad_n", C.c_int32), ("tally", C.c_int32),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libsans.so is not built ({LIB_PATH}); run "
+                          "`python -m paper_2501_06054_amd.build` (or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    vp, i32, u32, u64, i64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_int64
+    L.sans_model_create.argtypes = [P(sans_params), P(vp)]
+    L.sans_model_destroy.argtypes = [vp]
+    L.sans_trace.argtypes = [vp, u64, u64, P(sans_params), vp, vp]
+    L.sans_trace_ex.argtypes = [vp, u64, u64, u64, u32, u32, vp, vp, vp, vp]
+    L.sans_debug_trace.argtypes = [vp, u64, u64, u64, u32, vp, vp, vp, vp]
+    L.sans_debug_philox.argtypes = [u64, u64, u64, u32, u32, vp, vp]
+    L.sans_debug_table.argtypes = [vp, i32, P(C.c_float), i32]
+    L.sans_pq_avg.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.sans_model_constants.argtypes = [vp, P(C.c_double)]
+    L.sans_abi_params_size.restype = u32
+    L.sans_status_string.argtypes = [C.c_int]
+    L.sans_status_string.restype = C.c_char_p
+    L.sans_last_error.restype = C.c_char_p
+    for f in ("sans_model_create", "sans_model_destroy", "sans_trace", "sans_trace_ex",
+              "sans_debug_trace", "sans_debug_philox", "sans_debug_table", "sans_pq_avg",
+              "sans_model_constants"):
+        getattr(L, f).restype = C.c_int
+    return L
+
+
+lib = _load()
+
+
+def _check(rc: int, where: str):
+    if rc != SANS_OK:
+        raise SansError(rc, where, lib.sans_last_error().decode())
+
+
+def _dev(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def to_params(p: dict, tally: str = "auto") -> sans_params:
+    """Workload parameter dict (paper_2501_06054_amd.workloads) -> sans_params."""
+    s = sans_params()
+    s.abi_version = SANS_ABI_VERSION
+    s.kind = KIND[p["kind"]]
+    s.mode = MODE[p["mode"]]
+    s.orient_kind = ORIENT[p["orient_kind"]]
+    for k in range(3):
+        s.size[k] = p["size"][k]
+        s.sld[k] = p["sld"][k]
+        s.orient_mean[k] = p["orient_mean"][k]
+        s.orient_sigma[k] = p["orient_sigma"][k]
+    for f in ("shell", "phi", "sq_phi", "sq_radius", "poly", "src_w", "src_h", "src_z",
+              "slit_w", "slit_h", "slit_z", "lambda0", "dlambda_rel", "cone_alpha",
+              "sample_w", "sample_h", "sample_d", "det_w", "det_h", "det_z"):
+        setattr(s, f, float(p[f]))
+    s.poly_mask = int(p["poly_mask"])
+    s.table_size = int(p["table_size"])
+    s.nx, s.ny = int(p["nx"]), int(p["ny"])
+    s.quad_n = int(p["quad_n"])
+    s.tally = TALLY[p.get("tally", tally)]
+    return s
+
+
+# ---------------------------------------------------------------- C ABI mirror
+
+def sans_model_create(params) -> C.c_void_p:
+    sp = params if isinstance(params, sans_params) else to_params(params)
+    h = C.c_void_p()
+    _check(lib.sans_model_create(C.byref(sp), C.byref(h)), "sans_model_create")
+    return h
+
+
+def sans_model_destroy(h) -> None:
+    _check(lib.sans_model_destroy(h), "sans_model_destroy")
+
+
+def sans_trace(h, n_neutrons: int, seed: int, params, detector_out, stream=None) -> None:
+    sp = None
+    if params is not None:
+        sp = params if isinstance(params, sans_params) else to_params(params)
+    _check(lib.sans_trace(h, n_neutrons, seed, C.byref(sp) if sp is not None else None,
+                          _dev(detector_out, torch.float64, "detector_out"), _stream(stream)),
+           "sans_trace")
+
+
+def sans_trace_ex(h, first: int, n: int, seed: int, exp_id: int, flags: int, det,
+                  det_w2=None, det_count=None, stream=None) -> None:
+    _check(lib.sans_trace_ex(h, first, n, seed, exp_id, flags, _dev(det, torch.float64, "det"),
+                             _dev(det_w2, torch.float64, "det_w2"),
+                             _dev(det_count, torch.int64, "det_count"), _stream(stream)),
+           "sans_trace_ex")
+
+
+def sans_debug_trace(h, first: int, n: int, seed: int, exp_id: int, pixel=None, w=None, q=None,
+                     stream=None) -> None:
+    _check(lib.sans_debug_trace(h, first, n, seed, exp_id, _dev(pixel, torch.int32, "pixel"),
+                                _dev(w, torch.float32, "w"), _dev(q, torch.float32, "q"),
+                                _stream(stream)), "sans_debug_trace")
+
+
+def sans_debug_philox(seed: int, first: int, n: int, n_blocks: int, exp_id: int, out,
+                      stream=None) -> None:
+    _check(lib.sans_debug_philox(seed, first, n, n_blocks, exp_id, _dev(out, torch.int32, "out"),
+                                 _stream(stream)), "sans_debug_philox")
+
+
+def sans_debug_table(h, which: int, n: int):
+    import numpy as np
+    out = np.zeros(n, dtype=np.float32)
+    _check(lib.sans_debug_table(h, which, out.ctypes.data_as(C.POINTER(C.c_float)), n),
+           "sans_debug_table")
+    return out
+
+
+def sans_pq_avg(h, q, qvec, out, stream=None) -> None:
+    _check(lib.sans_pq_avg(h, _dev(q, torch.float32, "q"), _dev(qvec, torch.float32, "qvec"),
+                           q.numel(), _dev(out, torch.float32, "out"), _stream(stream)),
+           "sans_pq_avg")
+
+
+def sans_model_constants(h):
+    out = (C.c_double * 3)()
+    _check(lib.sans_model_constants(h, out), "sans_model_constants")
+    return tuple(out)
+
+
+def sans_abi_params_size() -> int:
+    return int(lib.sans_abi_params_size())
+
+
+# ---------------------------------------------------------------- convenience
+
+class Model:
+    """Owns a model handle; destroyed on close() / garbage collection."""
+
+    def __init__(self, params: dict, tally: str = "auto"):
+        self.params = dict(params)
+        self.handle = sans_model_create(to_params(params, tally))
+
+    def close(self):
+        if self.handle is not None:
+            sans_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def detector(self):
+        return torch.zeros((self.params["ny"], self.params["nx"]), dtype=torch.float64,
+                           device="cuda")
+
+    def trace(self, n: int, seed: int, det=None, first: int = 0, exp_id: int = 0,
+              accumulate: bool = False, det_w2=None, det_count=None, stream=None):
+        if det is None:
+            det = self.detector()
+        sans_trace_ex(self.handle, first, n, seed, exp_id, SANS_ACCUMULATE if accumulate else 0,
+                      det, det_w2, det_count, stream)
+        return det
+
+    def debug_trace(self, n: int, seed: int, first: int = 0, exp_id: int = 0):
+        pix = torch.empty(n, dtype=torch.int32, device="cuda")
+        w = torch.empty(n, dtype=torch.float32, device="cuda")
+        q = torch.empty(n, dtype=torch.float32, device="cuda")
+        sans_debug_trace(self.handle, first, n, seed, exp_id, pix, w, q)
+        return pix, w, q
+
+    def pq_avg(self, q, qvec=None):
+        out = torch.empty_like(q)
+        sans_pq_avg(self.handle, q, qvec, out)
+        return out
+
+    def constants(self):
+        return sans_model_constants(self.handle)

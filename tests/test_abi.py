@@ -1,0 +1,87 @@
+"""CPU-side checks of the C ABI: the library loads, exports every entry point
+declared in include/sans.h, agrees with the binding on the parameter layout,
+and rejects invalid parameters before touching the GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "sans.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*(sans_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2501_06054_amd import sans
+    return sans
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("sans_model_create", "sans_model_destroy", "sans_trace", "sans_trace_ex",
+                 "sans_debug_trace", "sans_debug_philox", "sans_pq_avg", "sans_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(S):
+    for name in declared_functions():
+        assert hasattr(S.lib, name), name
+
+
+def test_params_layout_matches(S):
+    assert S.sans_abi_params_size() == C.sizeof(S.sans_params)
+
+
+def test_status_strings(S):
+    assert S.lib.sans_status_string(0) == b"ok"
+    assert S.lib.sans_status_string(S.SANS_E_INVALID_ARG) == b"invalid argument"
+
+
+def _create_status(S, p):
+    h = C.c_void_p()
+    sp = S.to_params(p)
+    return S.lib.sans_model_create(C.byref(sp), C.byref(h)), sp
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(size=(-1.0, 0, 0)), -1),
+    (dict(phi=1.5), -1),
+    (dict(sq_phi=0.7), -1),
+    (dict(poly=-0.1), -1),
+    (dict(table_size=10), -1),
+    (dict(nx=0), -1),
+    (dict(cone_alpha=0.0), -1),
+    (dict(kind="cylinder", size=(20.0, 0.0, 0.0)), -1),
+    (dict(mode="surrogate"), -2),
+    (dict(kind="cylinder", size=(20.0, 40.0, 0.0), mode="quad", orient_kind="gaussian"), -2),
+])
+def test_invalid_params_rejected_without_gpu(S, over, status):
+    from paper_2501_06054_amd import workloads as W
+    p = W.params(**over)
+    rc, _ = _create_status(S, p)
+    assert rc == status
+    assert len(S.lib.sans_last_error()) > 0
+
+
+def test_abi_version_checked(S):
+    from paper_2501_06054_amd import workloads as W
+    sp = S.to_params(W.params())
+    sp.abi_version = 99
+    h = C.c_void_p()
+    assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_INVALID_ARG
+
+
+def test_null_arguments(S):
+    assert S.lib.sans_model_create(None, None) == S.SANS_E_INVALID_ARG
+    assert S.lib.sans_trace(None, 10, 1, None, None, None) == S.SANS_E_INVALID_ARG
+    assert S.lib.sans_debug_philox(1, 0, 10, 2, 0, None, None) == S.SANS_E_INVALID_ARG
+    assert S.lib.sans_model_destroy(None) == S.SANS_OK

@@ -1,0 +1,296 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs and the same Philox streams.
+
+Tolerances (the build's stated bar):
+  - random streams, pixel indices, hit patterns: bit-exact;
+  - per-neutron weight: |dw| <= 1e-5 * w_max + 1e-4 * |w|;
+  - total detected intensity: 1e-6 relative;
+  - every nonzero pixel: 1e-4 relative.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2501_06054_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2501_06054_amd import sans
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return sans
+
+
+def check_weights(w_gpu, w_orc, where=""):
+    w_gpu = np.asarray(w_gpu, dtype=np.float64)
+    wmax = np.max(np.abs(w_orc)) if w_orc.size else 0.0
+    tol = 1e-5 * wmax + 1e-4 * np.abs(w_orc)
+    bad = np.abs(w_gpu - w_orc) > tol
+    assert not bad.any(), (f"{where}: {bad.sum()} weights out of tolerance; worst "
+                           f"{np.max(np.abs(w_gpu - w_orc) / np.maximum(tol, 1e-300)):.3g} x tol")
+
+
+def check_detector(d_gpu, d_orc, where=""):
+    d_gpu = np.asarray(d_gpu)
+    assert d_gpu.shape == d_orc.shape
+    # same set of hit pixels
+    assert np.array_equal(d_gpu != 0, d_orc != 0), f"{where}: hit patterns differ"
+    tot_g, tot_o = d_gpu.sum(), d_orc.sum()
+    assert abs(tot_g - tot_o) <= 1e-6 * abs(tot_o), f"{where}: total {tot_g} vs {tot_o}"
+    nz = d_orc != 0
+    rel = np.abs(d_gpu[nz] - d_orc[nz]) / np.abs(d_orc[nz])
+    assert rel.max() <= 1e-4 if rel.size else True, f"{where}: worst pixel rel {rel.max():.3g}"
+
+
+# ------------------------------------------------------------------ streams
+
+@pytest.mark.parametrize("seed,first,n,nb,e", [
+    (1, 0, 5000, 3, 0),
+    (2**63 + 12345, 2**32 - 100, 300, 3, 4095),
+    (0xFFFFFFFFFFFFFFFF, 2**40 + 7, 257, 2, 7),
+])
+def test_philox_streams_bit_exact(S, seed, first, n, nb, e):
+    log(f"philox seed={seed} first={first} n={n}")
+    out = torch.empty((n, nb, 4), dtype=torch.int32, device="cuda")
+    S.sans_debug_philox(seed, first, n, nb, e, out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy().view(np.uint32)
+    ref = oracle.philox_stream(seed, first, n, nb, e)
+    assert np.array_equal(g, ref)
+
+
+# ------------------------------------------------------------------ tables
+
+@pytest.mark.parametrize("poly", [0.05, 0.2, 0.3])
+def test_tables_match_oracle(S, poly):
+    p = W.params(kind="cylinder", size=(20, 400, 0), poly=poly, poly_mask=1,
+                 orient_kind="gaussian", orient_sigma=(0.1, 0.1, 0.1))
+    m = S.Model(p)
+    M = p["table_size"]
+    tn = S.sans_debug_table(m.handle, 0, M)
+    ts = S.sans_debug_table(m.handle, 1, M)
+    on = oracle.table_normal(M)
+    os_ = oracle.table_schulz(M, poly)
+    assert np.allclose(tn, on, rtol=2e-7, atol=1e-7)
+    assert np.allclose(ts, os_, rtol=2e-7, atol=1e-9)
+    m.close()
+
+
+# ------------------------------------------------------------------ per neutron
+
+PER_NEUTRON = {
+    "tiny_sphere": (W.workload("tiny_sphere")["params"], 50021),
+    "coreshell_py": (W.workload("coreshell_py")["params"], 50021),
+    "oriented_cylinder": (W.workload("oriented_cylinder")["params"], 50021),
+    "oriented_ellipsoid": (W.workload("oriented_ellipsoid")["params"], 50021),
+    "iso_parallelepiped": (W.params(kind="parallelepiped", size=(20, 40, 120),
+                                    orient_kind="isotropic"), 30011),
+    "poly_cylinder_uniform_angles": (W.params(kind="cylinder", size=(30, 200, 0), poly=0.1,
+                                              poly_mask=3, orient_kind="uniform_angles"), 30011),
+    "fixed_cylinder": (W.params(kind="cylinder", size=(120, 200, 0),
+                                orient_mean=(math.pi / 3, math.pi / 3, 0)), 30011),
+    "poly_ellipsoid_py": (W.params(kind="ellipsoid", size=(30, 50, 90), poly=0.25, poly_mask=7,
+                                   sq_phi=0.3, sq_radius=45.0, phi=0.3,
+                                   orient_kind="isotropic"), 30011),
+    "big_sphere_py": (W.params(kind="sphere", size=(300, 0, 0), poly=0.3, sq_phi=0.45,
+                               sq_radius=300.0, phi=0.45), 30011),
+    "quad_parallelepiped": (dict(W.workload("quad_parallelepiped")["params"]), 601),
+    "quad_spheroid": (dict(W.workload("quad_spheroid")["params"]), 601),
+    "quad_coreshell": (W.params(kind="core_shell", mode="quad", size=(40, 0, 0), shell=10,
+                                sld=(1e-6, 3e-6, 6.3e-6), poly=0.2, sq_phi=0.2,
+                                sq_radius=50.0, phi=0.2), 2003),
+    "quad_fixed_cylinder": (W.params(kind="cylinder", mode="quad", size=(20, 400, 0), poly=0.1,
+                                     orient_mean=(math.pi / 2, 0, 0)), 2003),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PER_NEUTRON))
+@pytest.mark.parametrize("first", [0, 2**33 + 5])
+def test_per_neutron_parity(S, name, first):
+    p, n = PER_NEUTRON[name]
+    seed = 77
+    log(f"per-neutron {name} first={first} n={n}")
+    m = S.Model(p)
+    pix, w, q = m.debug_trace(n, seed, first=first)
+    torch.cuda.synchronize()
+    opix, ow, oq = oracle.trace_debug(p, n, seed, first=first)
+    assert np.array_equal(pix.cpu().numpy(), opix)
+    check_weights(w.cpu().numpy(), ow, name)
+    assert np.allclose(q.cpu().numpy(), oq, rtol=2e-7, atol=0)
+    m.close()
+
+
+# ------------------------------------------------------------------ detectors
+
+DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellipsoid",
+             "iso_parallelepiped", "poly_ellipsoid_py"]
+
+
+@pytest.mark.parametrize("name", DET_CASES)
+@pytest.mark.parametrize("tally", ["auto", "global", "lds", "xcd"])
+def test_detector_parity(S, name, tally):
+    p, _ = PER_NEUTRON[name]
+    n, seed = 300_007, 5
+    log(f"detector {name} tally={tally} n={n}")
+    m = S.Model(p, tally=tally)
+    det = m.trace(n, seed)
+    torch.cuda.synchronize()
+    ref = oracle.trace(p, n, seed, nthreads=NTHREADS)
+    check_detector(det.cpu().numpy(), ref, f"{name}/{tally}")
+    m.close()
+
+
+def test_quad_detector_parity(S):
+    p = W.workload("quad_parallelepiped")["params"]
+    n, seed = 6007, 6
+    m = S.Model(p)
+    det = m.trace(n, seed)
+    torch.cuda.synchronize()
+    ref = oracle.trace(p, n, seed, nthreads=NTHREADS)
+    check_detector(det.cpu().numpy(), ref, "quad_parallelepiped")
+    m.close()
+
+
+def test_pq_avg_matches_oracle(S):
+    for name in ("quad_parallelepiped", "quad_spheroid", "quad_coreshell"):
+        p, _ = PER_NEUTRON[name]
+        m = S.Model(p)
+        qs = np.concatenate([np.linspace(0.0, 0.06, 61), np.geomspace(1e-4, 0.3, 40)])
+        qt = torch.tensor(qs, dtype=torch.float32, device="cuda")
+        out = m.pq_avg(qt).cpu().numpy()
+        ref = np.array([oracle.pq_avg(p, float(np.float32(x))) for x in qs])
+        check_weights(out, ref, name)
+        m.close()
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_zero_neutrons_clears_detector(S):
+    p = W.workload("tiny_sphere")["params"]
+    m = S.Model(p)
+    det = torch.full((128, 128), 3.0, dtype=torch.float64, device="cuda")
+    m.trace(0, 1, det=det)
+    torch.cuda.synchronize()
+    assert float(det.abs().sum()) == 0.0
+    # accumulate with zero neutrons leaves the detector alone
+    det.fill_(2.0)
+    m.trace(0, 1, det=det, accumulate=True)
+    torch.cuda.synchronize()
+    assert float(det.sum()) == 2.0 * 128 * 128
+    m.close()
+
+
+@pytest.mark.parametrize("n", [1, 255, 257, 1000003])
+def test_ragged_counts(S, n):
+    p = W.workload("coreshell_py")["params"]
+    m = S.Model(p)
+    det = m.trace(n, 9)
+    torch.cuda.synchronize()
+    ref = oracle.trace(p, n, 9, nthreads=NTHREADS)
+    check_detector(det.cpu().numpy(), ref, f"n={n}")
+    m.close()
+
+
+def test_chunked_and_far_ranges(S):
+    p = W.workload("oriented_cylinder")["params"]
+    m = S.Model(p)
+    first = 2**40 - 12345
+    whole = m.trace(200_000, 3, first=first)
+    parts = m.trace(70_000, 3, first=first)
+    m.trace(130_000, 3, first=first + 70_000, det=parts, accumulate=True)
+    torch.cuda.synchronize()
+    a, b = whole.cpu().numpy(), parts.cpu().numpy()
+    assert np.allclose(a, b, rtol=1e-12, atol=0)
+    ref = oracle.trace(p, 200_000, 3, first=first, nthreads=NTHREADS)
+    check_detector(a, ref, "far range")
+    m.close()
+
+
+def test_experiment_id_and_w2_count(S):
+    p = W.workload("coreshell_py")["params"]
+    m = S.Model(p)
+    det = m.detector()
+    w2 = m.detector()
+    cnt = torch.zeros_like(det, dtype=torch.int64)
+    m.trace(100_003, 11, det=det, exp_id=17, det_w2=w2, det_count=cnt)
+    torch.cuda.synchronize()
+    r, rw2, rc = oracle.trace(p, 100_003, 11, exp_id=17, nthreads=NTHREADS, with_w2=True,
+                              with_count=True)
+    check_detector(det.cpu().numpy(), r, "exp 17")
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint64), rc)
+    nz = rw2 != 0
+    assert np.allclose(w2.cpu().numpy()[nz], rw2[nz], rtol=2e-4)
+    m.close()
+
+
+def test_params_update_in_trace(S):
+    p = W.workload("tiny_sphere")["params"]
+    m = S.Model(p)
+    p2 = dict(p, kind="ellipsoid", size=(20.0, 40.0, 60.0), orient_kind="isotropic")
+    det = m.detector()
+    S.sans_trace(m.handle, 50_000, 4, p2, det)
+    torch.cuda.synchronize()
+    ref = oracle.trace(p2, 50_000, 4, nthreads=NTHREADS)
+    check_detector(det.cpu().numpy(), ref, "params replaced")
+    m.close()
+
+
+# ------------------------------------------------------------------ full sizes
+
+def test_full_size_coreshell(S):
+    """The core-shell + Percus-Yevick workload at its full 1e8 neutrons, in
+    the launch configuration the benchmark times, against the oracle."""
+    wl = W.workload("coreshell_py")
+    p, n, seed = wl["params"], wl["n"], wl["seed"]
+    log(f"full-size coreshell n={n} oracle threads={NTHREADS}")
+    m = S.Model(p)
+    det = m.trace(n, seed)
+    torch.cuda.synchronize()
+    ref = oracle.trace(p, n, seed, nthreads=NTHREADS)
+    check_detector(det.cpu().numpy(), ref, "coreshell 1e8")
+    m.close()
+
+
+@pytest.mark.parametrize("name", ["oriented_cylinder", "oriented_ellipsoid"])
+def test_full_size_sampled(S, name):
+    """1e9-neutron workloads: the full run equals the sum of its chunks, and
+    windows spread over the whole index range match the oracle neutron by
+    neutron."""
+    wl = W.workload(name)
+    p, n, seed = wl["params"], wl["n"], wl["seed"]
+    log(f"full-size sampled {name} n={n}")
+    m = S.Model(p)
+    full = m.trace(n, seed)
+    parts = m.detector()
+    step = n // 8
+    for c in range(8):
+        m.trace(step, seed, first=c * step, det=parts, accumulate=True)
+    torch.cuda.synchronize()
+    a, b = full.cpu().numpy(), parts.cpu().numpy()
+    assert np.allclose(a, b, rtol=1e-9, atol=0)
+    rng = np.random.default_rng(1)
+    for first in rng.integers(0, n - 4096, size=8):
+        pix, w, _ = m.debug_trace(4096, seed, first=int(first))
+        opix, ow, _ = oracle.trace_debug(p, 4096, seed, first=int(first))
+        assert np.array_equal(pix.cpu().numpy(), opix)
+        check_weights(w.cpu().numpy(), ow, f"{name}@{first}")
+    # the first 5e6 neutrons as a whole detector
+    head = m.trace(5_000_000, seed)
+    torch.cuda.synchronize()
+    ref = oracle.trace(p, 5_000_000, seed, nthreads=NTHREADS)
+    check_detector(head.cpu().numpy(), ref, f"{name} head")
+    m.close()
