@@ -33,6 +33,11 @@ constexpr double lam_coef(int m) { return (m % 2 ? -1.0 : 1.0) / (cpow4(m) * cfa
 // Taylor coefficients in x^2 of sin(x)/x: (-1)^m / (2m+1)!
 constexpr double sinc_coef(int m) { return (m % 2 ? -1.0 : 1.0) / cfact(2 * m + 1); }
 
+// Forced compile-time evaluation of the coefficients (no run-time calls).
+template <int M> struct SphC { static constexpr float v = (float)sph_coef(M); };
+template <int M> struct LamC { static constexpr float v = (float)lam_coef(M); };
+template <int M> struct SincC { static constexpr float v = (float)sinc_coef(M); };
+
 constexpr int kPySeriesTerms = 12;
 constexpr int kMaxQuad = 256;
 
@@ -123,14 +128,14 @@ __device__ __forceinline__ float sph3j(float x)
     x = fabsf(x);
     if (x < 2.0f) {
         const float x2 = x * x;
-        float r = (float)sph_coef(8);
-        r = __builtin_fmaf(r, x2, (float)sph_coef(7));
-        r = __builtin_fmaf(r, x2, (float)sph_coef(6));
-        r = __builtin_fmaf(r, x2, (float)sph_coef(5));
-        r = __builtin_fmaf(r, x2, (float)sph_coef(4));
-        r = __builtin_fmaf(r, x2, (float)sph_coef(3));
-        r = __builtin_fmaf(r, x2, (float)sph_coef(2));
-        r = __builtin_fmaf(r, x2, (float)sph_coef(1));
+        float r = SphC<8>::v;
+        r = __builtin_fmaf(r, x2, SphC<7>::v);
+        r = __builtin_fmaf(r, x2, SphC<6>::v);
+        r = __builtin_fmaf(r, x2, SphC<5>::v);
+        r = __builtin_fmaf(r, x2, SphC<4>::v);
+        r = __builtin_fmaf(r, x2, SphC<3>::v);
+        r = __builtin_fmaf(r, x2, SphC<2>::v);
+        r = __builtin_fmaf(r, x2, SphC<1>::v);
         return __builtin_fmaf(r, x2, 1.0f);
     }
     float s, c;
@@ -145,9 +150,16 @@ __device__ __forceinline__ float lambda1(float x)
     x = fabsf(x);
     if (x < 3.0f) {
         const float x2 = x * x;
-        float r = (float)lam_coef(10);
-#pragma unroll
-        for (int m = 9; m >= 1; --m) r = __builtin_fmaf(r, x2, (float)lam_coef(m));
+        float r = LamC<10>::v;
+        r = __builtin_fmaf(r, x2, LamC<9>::v);
+        r = __builtin_fmaf(r, x2, LamC<8>::v);
+        r = __builtin_fmaf(r, x2, LamC<7>::v);
+        r = __builtin_fmaf(r, x2, LamC<6>::v);
+        r = __builtin_fmaf(r, x2, LamC<5>::v);
+        r = __builtin_fmaf(r, x2, LamC<4>::v);
+        r = __builtin_fmaf(r, x2, LamC<3>::v);
+        r = __builtin_fmaf(r, x2, LamC<2>::v);
+        r = __builtin_fmaf(r, x2, LamC<1>::v);
         return __builtin_fmaf(r, x2, 1.0f);
     }
     return 2.0f * j1f(x) * rcpf(x);
@@ -159,10 +171,10 @@ __device__ __forceinline__ float sincf(float x)
     const float ax = fabsf(x);
     if (ax < 0.5f) {
         const float x2 = x * x;
-        float r = (float)sinc_coef(4);
-        r = __builtin_fmaf(r, x2, (float)sinc_coef(3));
-        r = __builtin_fmaf(r, x2, (float)sinc_coef(2));
-        r = __builtin_fmaf(r, x2, (float)sinc_coef(1));
+        float r = SincC<4>::v;
+        r = __builtin_fmaf(r, x2, SincC<3>::v);
+        r = __builtin_fmaf(r, x2, SincC<2>::v);
+        r = __builtin_fmaf(r, x2, SincC<1>::v);
         return __builtin_fmaf(r, x2, 1.0f);
     }
     return sinf(ax) * rcpf(ax);
