@@ -60,7 +60,8 @@ struct TraceArgs {
     float contrast;               // drho = sld[0] - sld[2]
     float cs_core, cs_shell;      // core-shell: sld0 - sld1, sld1 - sld2
     int32_t poly_on, poly_mask, orient_kind, third_block;
-    float ang_mean[3], ang_sigma[3];
+    float ang_sin[3], ang_cos[3];  // sin, cos of the mean angles (FP64 on the host)
+    float ang_sigma[3];
     int32_t sq_on;
     float sq_2r, sq_24phi;
     float py_alpha, py_beta, py_gamma;
@@ -250,23 +251,33 @@ __device__ __forceinline__ float amplitude(const TraceArgs& a, const float s[3],
     }
 }
 
-// Particle axes A = R x, B = R y, C = R z with R = Rz(phi) Ry(theta) Rz(Psi).
-__device__ __forceinline__ void particle_axes(float th, float ph, float ps, float A[3], float B[3],
-                                              float C[3])
-{
+// Particle axes A = R x, B = R y, C = R z with R = Rz(phi) Ry(theta) Rz(Psi),
+// from the sines and cosines of (theta, phi, Psi).
+struct Trig3 {
     float st, ct, sp, cp, ss, cs;
-    sincosf(th, &st, &ct);
-    sincosf(ph, &sp, &cp);
-    sincosf(ps, &ss, &cs);
-    A[0] = cp * ct * cs - sp * ss;
-    A[1] = sp * ct * cs + cp * ss;
-    A[2] = -st * cs;
-    B[0] = -cp * ct * ss - sp * cs;
-    B[1] = -sp * ct * ss + cp * cs;
-    B[2] = st * ss;
-    C[0] = cp * st;
-    C[1] = sp * st;
-    C[2] = ct;
+};
+
+__device__ __forceinline__ void particle_axes(const Trig3& g, float A[3], float B[3], float C[3])
+{
+    A[0] = g.cp * g.ct * g.cs - g.sp * g.ss;
+    A[1] = g.sp * g.ct * g.cs + g.cp * g.ss;
+    A[2] = -g.st * g.cs;
+    B[0] = -g.cp * g.ct * g.ss - g.sp * g.cs;
+    B[1] = -g.sp * g.ct * g.ss + g.cp * g.cs;
+    B[2] = g.st * g.ss;
+    C[0] = g.cp * g.st;
+    C[1] = g.sp * g.st;
+    C[2] = g.ct;
+}
+
+// sin and cos of (mean + d) from those of the mean (exact on the host) and of
+// the small offset d: keeps the rounding of the mean angle out of FP32.
+__device__ __forceinline__ void rotate_by(float sm, float cm, float d, float& s, float& c)
+{
+    float sd, cd;
+    sincosf(d, &sd, &cd);
+    s = __builtin_fmaf(sm, cd, cm * sd);
+    c = __builtin_fmaf(cm, cd, -sm * sd);
 }
 
 // ---------------------------------------------------------------- one neutron
@@ -363,23 +374,29 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     float f2;
     if constexpr (MODE == 0) {
         float y = 1.0f;
-        float th = a.ang_mean[0], ph = a.ang_mean[1], ps = a.ang_mean[2];
+        Trig3 g{a.ang_sin[0], a.ang_cos[0], a.ang_sin[1], a.ang_cos[1], a.ang_sin[2], a.ang_cos[2]};
         if (a.third_block) {
             const U4 r2 = philox4x32_10(ilo, ihi, 2u, a.exp_id, a.seed_lo, a.seed_hi);
             if (a.poly_on) y = fmaxf(table_lerp(tab_size, a.M, u32f(r2.x)), 0.0f);
             if constexpr (KIND >= kCylinder) {
                 if (a.orient_kind == 1) {
-                    th = __builtin_fmaf(a.ang_sigma[0], table_lerp(tab_norm, a.M, u32f(r2.y)), th);
-                    ph = __builtin_fmaf(a.ang_sigma[1], table_lerp(tab_norm, a.M, u32f(r2.z)), ph);
-                    ps = __builtin_fmaf(a.ang_sigma[2], table_lerp(tab_norm, a.M, u32f(r2.w)), ps);
+                    rotate_by(a.ang_sin[0], a.ang_cos[0],
+                              a.ang_sigma[0] * table_lerp(tab_norm, a.M, u32f(r2.y)), g.st, g.ct);
+                    rotate_by(a.ang_sin[1], a.ang_cos[1],
+                              a.ang_sigma[1] * table_lerp(tab_norm, a.M, u32f(r2.z)), g.sp, g.cp);
+                    rotate_by(a.ang_sin[2], a.ang_cos[2],
+                              a.ang_sigma[2] * table_lerp(tab_norm, a.M, u32f(r2.w)), g.ss, g.cs);
                 } else if (a.orient_kind == 2) {
-                    th = acosf(__builtin_fmaf(2.0f, u32f(r2.y), -1.0f));
-                    ph = 2.0f * (float)kPi * u32f(r2.z);
-                    ps = 2.0f * (float)kPi * u32f(r2.w);
+                    // cos(theta) uniform in [-1, 1]; phi, Psi uniform in [0, 2 pi)
+                    g.ct = __builtin_fmaf(2.0f, u32f(r2.y), -1.0f);
+                    g.st = sqrtf(fmaxf(__builtin_fmaf(-g.ct, g.ct, 1.0f), 0.0f));
+                    sincospif(2.0f * u32f(r2.z), &g.sp, &g.cp);
+                    sincospif(2.0f * u32f(r2.w), &g.ss, &g.cs);
                 } else if (a.orient_kind == 3) {
-                    th = (float)kPi * u32f(r2.y);
-                    ph = 2.0f * (float)kPi * u32f(r2.z);
-                    ps = 2.0f * (float)kPi * u32f(r2.w);
+                    // the literal rule: theta uniform in [0, pi)
+                    sincospif(u32f(r2.y), &g.st, &g.ct);
+                    sincospif(2.0f * u32f(r2.z), &g.sp, &g.cp);
+                    sincospif(2.0f * u32f(r2.w), &g.ss, &g.cs);
                 }
             }
         }
@@ -389,7 +406,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
         float qa = 0.0f, qb = 0.0f, qc = 0.0f;
         if constexpr (KIND >= kCylinder) {
             float A[3], B[3], C[3];
-            particle_axes(th, ph, ps, A, B, C);
+            particle_axes(g, A, B, C);
             qc = qv[0] * C[0] + qv[1] * C[1] + qv[2] * C[2];
             if constexpr (KIND != kCylinder) {
                 qa = qv[0] * A[0] + qv[1] * A[1] + qv[2] * A[2];
@@ -435,7 +452,9 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* l
             float qa = 0.0f, qb = 0.0f, qc = 0.0f;
             if constexpr (KIND >= kCylinder) {
                 float A[3], B[3], C[3];
-                particle_axes(a.ang_mean[0], a.ang_mean[1], a.ang_mean[2], A, B, C);
+                const Trig3 g{a.ang_sin[0], a.ang_cos[0], a.ang_sin[1], a.ang_cos[1], a.ang_sin[2],
+                              a.ang_cos[2]};
+                particle_axes(g, A, B, C);
                 qa = qv[0] * A[0] + qv[1] * A[1] + qv[2] * A[2];
                 qb = qv[0] * B[0] + qv[1] * B[1] + qv[2] * B[2];
                 qc = qv[0] * C[0] + qv[1] * C[1] + qv[2] * C[2];

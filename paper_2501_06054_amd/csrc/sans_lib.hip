@@ -385,7 +385,8 @@ int configure(sans_model_s* m, const sans_params* p)
     a.wscale = m->wscale;
     for (int k = 0; k < 3; ++k) {
         a.size[k] = (float)p->size[k];
-        a.ang_mean[k] = (float)p->orient_mean[k];
+        a.ang_sin[k] = (float)std::sin(p->orient_mean[k]);
+        a.ang_cos[k] = (float)std::cos(p->orient_mean[k]);
         a.ang_sigma[k] = (float)p->orient_sigma[k];
     }
     a.shell = (float)p->shell;
