@@ -151,7 +151,7 @@ typedef struct {
 typedef struct sans_model_s* sans_model_t;
 
 /* Validates p, builds the inverse-CDF tables (standard normal and Schulz
- * quantiles at (k + 1/2)/M, FP64 on the host, stored as FP32 on the device)
+ * quantiles at (k + 1/2)/M, FP64, staged in LDS by the kernels)
  * and the model constants.  *out receives an opaque handle owning its device
  * buffers.  Errors: SANS_E_INVALID_ARG (null pointers, wrong abi_version, a
  * size <= 0, negative widths or spreads, phi or sq_phi outside [0, 1) / [0,
@@ -192,10 +192,10 @@ int sans_debug_trace(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed,
 int sans_debug_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t n_blocks,
                       uint32_t exp_id, uint32_t* out, void* stream);
 
-/* Copies the handle's FP32 table knots to host memory: which = 0 standard
- * normal, 1 Schulz.  out (host float [n]) with n = table_size.
+/* Copies the handle's FP64 table knots to host memory: which = 0 standard
+ * normal, 1 Schulz.  out (host double [n]) with n = table_size.
  * SANS_E_UNSUPPORTED if the handle has no such table. */
-int sans_debug_table(sans_model_t m, int32_t which, float* out, int32_t n);
+int sans_debug_table(sans_model_t m, int32_t which, double* out, int32_t n);
 
 /* Evaluates, on the device, the weight factor F^2 that replaces the drawn
  * size and orientation in SANS_MODE_QUAD: the Schulz size average and, for

@@ -91,6 +91,8 @@ def lib():
         L.orc_trace.restype = i32
         L.orc_trace_debug.argtypes = [P(OrcParams), u64, u64, u64, u32, P(i32), P(d), P(d)]
         L.orc_trace_debug.restype = i32
+        L.orc_trace_debug_ex.argtypes = [P(OrcParams), u64, u64, u64, u32, P(d)]
+        L.orc_trace_debug_ex.restype = i32
         _LIB = L
     return _LIB
 
@@ -250,3 +252,14 @@ def trace_debug(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0):
     if rc != 0:
         raise ValueError(f"oracle trace failed ({rc})")
     return pix, w, q
+
+
+def trace_debug_ex(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0) -> np.ndarray:
+    """Per-neutron intermediates [n, 11]: pixel, w, q, Q_x, Q_y, Q_z, y,
+    theta, phi, Psi, path length (m)."""
+    o = to_params(p)
+    out = np.zeros((n, 11))
+    rc = lib().orc_trace_debug_ex(C.byref(o), first, n, seed, exp_id, _ptr(out, C.c_double))
+    if rc != 0:
+        raise ValueError(f"oracle trace failed ({rc})")
+    return out

@@ -585,6 +585,8 @@ typedef struct {
     int32_t pixel; /* -1: no tally */
     double w;
     double q;
+    /* intermediate values, for diagnostics */
+    double qv[3], y, ang[3], len;
 } orc_event;
 
 static int ctx_init(orc_ctx* cx, const orc_params* p)
@@ -620,7 +622,9 @@ static void ctx_free(orc_ctx* cx)
 static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_t e)
 {
     const orc_params* p = cx->p;
-    orc_event ev = {-1, 0.0, 0.0};
+    orc_event ev;
+    memset(&ev, 0, sizeof(ev));
+    ev.pixel = -1;
     uint32_t r0[4], r1[4], r2[4] = {0, 0, 0, 0};
     neutron_block(seed, i, 0, e, r0);
     neutron_block(seed, i, 1, e, r1);
@@ -712,6 +716,12 @@ static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_
     }
     double sq = (p->sq_phi > 0.0) ? orc_py_sq(q, p->sq_radius, p->sq_phi) : 1.0;
     double w = len * 1e10 * cx->prefactor * f2 * sq;
+    for (int a = 0; a < 3; ++a) {
+        ev.qv[a] = qv[a];
+        ev.ang[a] = ang[a];
+    }
+    ev.y = y;
+    ev.len = len;
 
     /* straight flight to the detector plane and the pixel hit */
     if (!(kf[2] > 0.0)) return ev;
@@ -736,6 +746,32 @@ int orc_trace_debug(const orc_params* p, uint64_t first, uint64_t n, uint64_t se
         if (pixel) pixel[j] = ev.pixel;
         if (w) w[j] = ev.w;
         if (q) q[j] = ev.q;
+    }
+    ctx_free(&cx);
+    return 0;
+}
+
+/* Per-neutron intermediate values (diagnostics): out[j*11 + k], k = pixel,
+ * w, q, Q_x, Q_y, Q_z, y, theta, phi, Psi, path length (m). */
+int orc_trace_debug_ex(const orc_params* p, uint64_t first, uint64_t n, uint64_t seed,
+                       uint32_t exp_id, double* out)
+{
+    orc_ctx cx;
+    if (ctx_init(&cx, p) != 0) return -1;
+    for (uint64_t j = 0; j < n; ++j) {
+        orc_event ev = trace_one(&cx, first + j, seed, exp_id);
+        double* o = out + j * 11;
+        o[0] = ev.pixel;
+        o[1] = ev.w;
+        o[2] = ev.q;
+        o[3] = ev.qv[0];
+        o[4] = ev.qv[1];
+        o[5] = ev.qv[2];
+        o[6] = ev.y;
+        o[7] = ev.ang[0];
+        o[8] = ev.ang[1];
+        o[9] = ev.ang[2];
+        o[10] = ev.len;
     }
     ctx_free(&cx);
     return 0;

@@ -6,13 +6,18 @@
 //   3. slab-sample entry and exit, scattering point (FP64);
 //   4. outgoing direction uniform in the cone, scattering vector Q (FP64);
 //   5. particle size and orientation from inverse-CDF tables staged in LDS
-//      (Methods, "Polydispersity and orientational distributions"), FP32;
+//      (Methods, "Polydispersity and orientational distributions");
 //   6. amplitude F of the model (Eqs. (5)-(7), (9)) and the hard-sphere
-//      Percus-Yevick S(Q), FP32 VALU;
+//      Percus-Yevick S(Q);
 //   7. weight w = l dOmega n F^2 S (Eq. (3) with n = phi/<V>), FP32;
 //   8. straight flight to the detector plane and the pixel index (FP64).
-// Geometry stays FP64 so that the pixel a neutron lands in does not depend
-// on rounding; the physics of the weight is FP32.
+//
+// Precision split.  Everything that is geometry -- positions, directions, Q,
+// the particle axes, the dimensionless phases x = Q.r that enter the shape
+// functions, and their reduction modulo pi/2 -- is FP64, so that a neutron's
+// pixel and the distance of its phase to a zero of F are exact to FP64
+// rounding.  The transcendentals (sin/cos polynomials on the reduced phase,
+// J1, the series) and the weight itself are FP32 VALU.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,6 +27,10 @@ namespace sans {
 
 // ---------------------------------------------------------------- constants
 constexpr double kPi = 3.141592653589793238462643383;
+// pi/2 split for Cody-Waite reduction (FP64 head + tail)
+constexpr double kPio2Hi = 1.5707963267948966;
+constexpr double kPio2Lo = 6.123233995736766e-17;
+constexpr double k2oPi = 0.6366197723675814;
 
 constexpr double cfact(int n) { return n <= 1 ? 1.0 : n * cfact(n - 1); }
 constexpr double cpow4(int m) { return m == 0 ? 1.0 : 4.0 * cpow4(m - 1); }
@@ -30,13 +39,17 @@ constexpr double cpow4(int m) { return m == 0 ? 1.0 : 4.0 * cpow4(m - 1); }
 constexpr double sph_coef(int m) { return (m % 2 ? -1.0 : 1.0) * 6.0 * (m + 1) / cfact(2 * m + 3); }
 // Taylor coefficients in x^2 of 2 J1(x)/x: (-1)^m / (4^m m! (m+1)!)
 constexpr double lam_coef(int m) { return (m % 2 ? -1.0 : 1.0) / (cpow4(m) * cfact(m) * cfact(m + 1)); }
-// Taylor coefficients in x^2 of sin(x)/x: (-1)^m / (2m+1)!
-constexpr double sinc_coef(int m) { return (m % 2 ? -1.0 : 1.0) / cfact(2 * m + 1); }
+// Taylor coefficients of sin and cos
+constexpr double sin_coef(int m) { return (m % 2 ? -1.0 : 1.0) / cfact(2 * m + 1); }
+constexpr double cos_coef(int m) { return (m % 2 ? -1.0 : 1.0) / cfact(2 * m); }
 
 // Forced compile-time evaluation of the coefficients (no run-time calls).
 template <int M> struct SphC { static constexpr float v = (float)sph_coef(M); };
 template <int M> struct LamC { static constexpr float v = (float)lam_coef(M); };
-template <int M> struct SincC { static constexpr float v = (float)sinc_coef(M); };
+template <int M> struct SinC { static constexpr float v = (float)sin_coef(M); };
+template <int M> struct CosC { static constexpr float v = (float)cos_coef(M); };
+template <int M> struct SinD { static constexpr double v = sin_coef(M); };
+template <int M> struct CosD { static constexpr double v = cos_coef(M); };
 
 constexpr int kPySeriesTerms = 12;
 constexpr int kMaxQuad = 256;
@@ -54,31 +67,27 @@ struct TraceArgs {
     double inv_px, inv_py;        // nx / det_w, ny / det_h
     double wscale;                // 1e10 * dOmega * phi / <V>  (per metre of path)
     int32_t nx, ny;
-    // sample, FP32
-    float size[3];
-    float shell;
+    // sample
+    double size[3];               // sizes (phases are formed in FP64)
+    double shell;
+    double ang_sin[3], ang_cos[3];// sin, cos of the mean angles
+    double ang_sigma[3];
     float contrast;               // drho = sld[0] - sld[2]
     float cs_core, cs_shell;      // core-shell: sld0 - sld1, sld1 - sld2
     int32_t poly_on, poly_mask, orient_kind, third_block;
-    float ang_sin[3], ang_cos[3];  // sin, cos of the mean angles (FP64 on the host)
-    float ang_sigma[3];
     int32_t sq_on;
     float sq_2r, sq_24phi;
     float py_alpha, py_beta, py_gamma;
     float py_c[kPySeriesTerms];
-    // tables (device global memory; kernels stage them in LDS)
+    // tables (device global memory, FP64 knots; kernels stage them in LDS)
     int32_t M;                    // knots per table
-    const float* tab_size;        // Schulz quantiles or nullptr
-    const float* tab_norm;        // normal quantiles or nullptr
-    // exact-average quadrature (QUAD mode)
+    const double* tab_size;       // Schulz quantiles or nullptr
+    const double* tab_norm;       // normal quantiles or nullptr
+    // exact-average quadrature (QUAD mode), FP32 nodes
     int32_t quad_n, quad_ny, quad_dims;   // orientation nodes, size nodes, 0/1/2-D orientation
-    const float* quad_mu;         // [quad_n] mu nodes
-    const float* quad_wmu;        // [quad_n]
-    const float* quad_cb;         // [quad_n] cos(beta) nodes
-    const float* quad_sb;         // [quad_n] sin(beta)
-    const float* quad_wb;         // [quad_n]
-    const float* quad_y;          // [quad_ny] size nodes
-    const float* quad_wy;         // [quad_ny] normalised Schulz weights
+    const float* quad_nodes;      // mu[n] wmu[n] cb[n] sb[n] wb[n] y[ny] wy[ny]
+    float fsize[3], fshell;       // FP32 copies for the quadrature loop
+    float fA[3], fB[3], fC[3];    // fixed-orientation particle axes (FP32)
     // run
     uint64_t first, n;
     uint32_t seed_lo, seed_hi, exp_id;
@@ -112,41 +121,108 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     return U4{c0, c1, c2, c3};
 }
 
-// (x + 1/2) 2^-32 - 1/2, exact in FP64 (both steps are exact).
+// (x + 1/2) 2^-32 - 1/2 and (x + 1/2) 2^-32, exact in FP64.
 __device__ __forceinline__ double centred_u(uint32_t x)
 {
     return __builtin_fma((double)x, 0x1p-32, 0x1p-33 - 0.5);
 }
 __device__ __forceinline__ double u64(uint32_t x) { return __builtin_fma((double)x, 0x1p-32, 0x1p-33); }
-__device__ __forceinline__ float u32f(uint32_t x) { return __builtin_fmaf((float)x, 0x1p-32f, 0x1p-33f); }
 
 // ---------------------------------------------------------------- FP32 math
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// 3 j1(x)/x, the normalised sphere amplitude (Eq. (5) for a sphere).
-__device__ __forceinline__ float sph3j(float x)
+// sin r and cos r for |r| <= pi/4 by their Taylor polynomials (degree 11 and
+// 12; truncation below 1e-11).
+__device__ __forceinline__ void sincos_poly(float r, float& s, float& c)
 {
-    x = fabsf(x);
-    if (x < 2.0f) {
-        const float x2 = x * x;
-        float r = SphC<8>::v;
-        r = __builtin_fmaf(r, x2, SphC<7>::v);
-        r = __builtin_fmaf(r, x2, SphC<6>::v);
-        r = __builtin_fmaf(r, x2, SphC<5>::v);
-        r = __builtin_fmaf(r, x2, SphC<4>::v);
-        r = __builtin_fmaf(r, x2, SphC<3>::v);
-        r = __builtin_fmaf(r, x2, SphC<2>::v);
-        r = __builtin_fmaf(r, x2, SphC<1>::v);
-        return __builtin_fmaf(r, x2, 1.0f);
-    }
-    float s, c;
-    sincosf(x, &s, &c);
-    const float ix = rcpf(x);
-    return 3.0f * (s - x * c) * (ix * ix * ix);
+    const float r2 = r * r;
+    float ps = SinC<5>::v;
+    ps = __builtin_fmaf(ps, r2, SinC<4>::v);
+    ps = __builtin_fmaf(ps, r2, SinC<3>::v);
+    ps = __builtin_fmaf(ps, r2, SinC<2>::v);
+    ps = __builtin_fmaf(ps, r2, SinC<1>::v);
+    s = __builtin_fmaf(ps * r2, r, r);
+    float pc = CosC<6>::v;
+    pc = __builtin_fmaf(pc, r2, CosC<5>::v);
+    pc = __builtin_fmaf(pc, r2, CosC<4>::v);
+    pc = __builtin_fmaf(pc, r2, CosC<3>::v);
+    pc = __builtin_fmaf(pc, r2, CosC<2>::v);
+    pc = __builtin_fmaf(pc, r2, CosC<1>::v);
+    c = __builtin_fmaf(pc, r2, 1.0f);
 }
 
-// 2 J1(x)/x (the cylinder's cross-section factor, Eq. (9)).
-__device__ __forceinline__ float lambda1(float x)
+// Quadrant rotation: (sin, cos) of n pi/2 + r from those of r.
+__device__ __forceinline__ void quadrant(int n, float sr, float cr, float& s, float& c)
+{
+    const bool odd = n & 1;
+    const float a = odd ? cr : sr, b = odd ? sr : cr;
+    s = (n & 2) ? -a : a;
+    c = ((n + 1) & 2) ? -b : b;
+}
+
+// sin and cos of an FP64 phase: Cody-Waite reduction by pi/2 in FP64, then
+// the FP32 polynomials.  Exact quadrant and remainder for |x| < 2^40.
+__device__ __forceinline__ void sincos_phase(double x, float& s, float& c)
+{
+    const double n = rint(x * k2oPi);
+    double r = __builtin_fma(-n, kPio2Hi, x);
+    r = __builtin_fma(-n, kPio2Lo, r);
+    float sr, cr;
+    sincos_poly((float)r, sr, cr);
+    quadrant((int)(int64_t)n, sr, cr, s, c);
+}
+
+// The same for an FP32 argument (quadrature loops): FP32 Cody-Waite.
+__device__ __forceinline__ void sincos_f(float x, float& s, float& c)
+{
+    const float n = rintf(x * (float)k2oPi);
+    float r = __builtin_fmaf(-n, 1.5707963705062866f, x);   // pi/2 rounded to FP32
+    r = __builtin_fmaf(-n, -4.3711388286737929e-08f, r);     // pi/2 minus that
+    float sr, cr;
+    sincos_poly(r, sr, cr);
+    quadrant((int)n, sr, cr, s, c);
+}
+
+// 3 j1(x)/x, the normalised sphere amplitude: series below 2, else from the
+// reduced phase.
+__device__ __forceinline__ float sph3j_series(float x)
+{
+    const float x2 = x * x;
+    float r = SphC<8>::v;
+    r = __builtin_fmaf(r, x2, SphC<7>::v);
+    r = __builtin_fmaf(r, x2, SphC<6>::v);
+    r = __builtin_fmaf(r, x2, SphC<5>::v);
+    r = __builtin_fmaf(r, x2, SphC<4>::v);
+    r = __builtin_fmaf(r, x2, SphC<3>::v);
+    r = __builtin_fmaf(r, x2, SphC<2>::v);
+    r = __builtin_fmaf(r, x2, SphC<1>::v);
+    return __builtin_fmaf(r, x2, 1.0f);
+}
+
+__device__ __forceinline__ float sph3j_d(double xd)
+{
+    xd = fabs(xd);
+    const float x = (float)xd;
+    if (x < 2.0f) return sph3j_series(x);
+    float s, c;
+    sincos_phase(xd, s, c);
+    const float ix = rcpf(x);
+    return 3.0f * __builtin_fmaf(-x, c, s) * (ix * ix * ix);
+}
+
+__device__ __forceinline__ float sph3j_f(float x)
+{
+    x = fabsf(x);
+    if (x < 2.0f) return sph3j_series(x);
+    float s, c;
+    sincos_f(x, s, c);
+    const float ix = rcpf(x);
+    return 3.0f * __builtin_fmaf(-x, c, s) * (ix * ix * ix);
+}
+
+// 2 J1(x)/x (the cylinder's cross-section factor, Eq. (9)): Taylor series
+// below 3, the device library's j1f above.
+__device__ __forceinline__ float lambda1_f(float x)
 {
     x = fabsf(x);
     if (x < 3.0f) {
@@ -166,19 +242,34 @@ __device__ __forceinline__ float lambda1(float x)
     return 2.0f * j1f(x) * rcpf(x);
 }
 
-// sin(x)/x (parallelepiped faces, cylinder length factor).
-__device__ __forceinline__ float sincf(float x)
+// sin(x)/x: series below 0.5, else from the reduced phase.
+__device__ __forceinline__ float sinc_series(float x)
 {
-    const float ax = fabsf(x);
-    if (ax < 0.5f) {
-        const float x2 = x * x;
-        float r = SincC<4>::v;
-        r = __builtin_fmaf(r, x2, SincC<3>::v);
-        r = __builtin_fmaf(r, x2, SincC<2>::v);
-        r = __builtin_fmaf(r, x2, SincC<1>::v);
-        return __builtin_fmaf(r, x2, 1.0f);
-    }
-    return sinf(ax) * rcpf(ax);
+    const float x2 = x * x;
+    float r = SinC<4>::v;
+    r = __builtin_fmaf(r, x2, SinC<3>::v);
+    r = __builtin_fmaf(r, x2, SinC<2>::v);
+    r = __builtin_fmaf(r, x2, SinC<1>::v);
+    return __builtin_fmaf(r, x2, 1.0f);
+}
+
+__device__ __forceinline__ float sinc_d(double xd)
+{
+    xd = fabs(xd);
+    const float x = (float)xd;
+    if (x < 0.5f) return sinc_series(x);
+    float s, c;
+    sincos_phase(xd, s, c);
+    return s * rcpf(x);
+}
+
+__device__ __forceinline__ float sinc_f(float x)
+{
+    x = fabsf(x);
+    if (x < 0.5f) return sinc_series(x);
+    float s, c;
+    sincos_f(x, s, c);
+    return s * rcpf(x);
 }
 
 // Percus-Yevick hard-sphere S(q): x = 2 q R, S = 1/(1 + 24 phi G(x)/x).
@@ -196,7 +287,7 @@ __device__ __forceinline__ float py_sq(const TraceArgs& a, float q)
         gx = r;
     } else {
         float s, c;
-        sincosf(x, &s, &c);
+        sincos_f(x, s, c);
         const float ix = rcpf(x);
         const float ix2 = ix * ix;
         const float x2 = x * x;
@@ -209,75 +300,200 @@ __device__ __forceinline__ float py_sq(const TraceArgs& a, float q)
     return rcpf(__builtin_fmaf(a.sq_24phi, gx, 1.0f));
 }
 
-// Linear interpolation in an inverse-CDF table (knots at (k + 1/2)/M).
-__device__ __forceinline__ float table_lerp(const float* tab, int M, float u)
+// Linear interpolation in an FP64 inverse-CDF table (knots at (k + 1/2)/M).
+__device__ __forceinline__ double table_lerp(const double* tab, int M, double u)
 {
-    const float s = __builtin_fmaf(u, (float)M, -0.5f);
-    float fk = floorf(s);
-    fk = fminf(fmaxf(fk, 0.0f), (float)(M - 2));
+    const double s = __builtin_fma(u, (double)M, -0.5);
+    double fk = floor(s);
+    fk = fmin(fmax(fk, 0.0), (double)(M - 2));
     const int k = (int)fk;
-    const float f = s - fk;
-    const float y0 = tab[k], y1 = tab[k + 1];
-    return __builtin_fmaf(f, y1 - y0, y0);
+    const double f = s - fk;
+    const double y0 = tab[k], y1 = tab[k + 1];
+    return __builtin_fma(f, y1 - y0, y0);
 }
 
-// ---------------------------------------------------------------- models
-enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParallelepiped = 4 };
-
-// F of one particle with sizes s and lab-frame projections (qa, qb, qc) of Q.
-template <int KIND>
-__device__ __forceinline__ float amplitude(const TraceArgs& a, const float s[3], float q, float qa,
-                                           float qb, float qc)
+// ---------------------------------------------------------------- orientation (FP64)
+// sin and cos of a small FP64 angle (|d| < 0.8: Taylor, degree 15/16),
+// otherwise the device library's FP64 sincos.
+__device__ __forceinline__ void sincos_small(double d, double& s, double& c)
 {
-    constexpr float k43pi = (float)(4.0 / 3.0 * kPi);
-    if constexpr (KIND == kSphere) {
-        const float r = s[0];
-        return a.contrast * k43pi * r * r * r * sph3j(q * r);
-    } else if constexpr (KIND == kCoreShell) {
-        const float rc = s[0], ro = s[0] + a.shell;
-        return a.cs_core * k43pi * rc * rc * rc * sph3j(q * rc)
-             + a.cs_shell * k43pi * ro * ro * ro * sph3j(q * ro);
-    } else if constexpr (KIND == kCylinder) {
-        const float r = s[0], len = s[1];
-        const float qab = sqrtf(fmaxf(__builtin_fmaf(q, q, -qc * qc), 0.0f));
-        return a.contrast * (float)kPi * r * r * len * sincf(0.5f * qc * len) * lambda1(qab * r);
-    } else if constexpr (KIND == kEllipsoid) {
-        const float xa = qa * s[0], xb = qb * s[1], xc = qc * s[2];
-        const float x = sqrtf(xa * xa + xb * xb + xc * xc);
-        return a.contrast * k43pi * s[0] * s[1] * s[2] * sph3j(x);
+    if (fabs(d) < 0.8) {
+        const double d2 = d * d;
+        double ps = SinD<7>::v;
+        ps = __builtin_fma(ps, d2, SinD<6>::v);
+        ps = __builtin_fma(ps, d2, SinD<5>::v);
+        ps = __builtin_fma(ps, d2, SinD<4>::v);
+        ps = __builtin_fma(ps, d2, SinD<3>::v);
+        ps = __builtin_fma(ps, d2, SinD<2>::v);
+        ps = __builtin_fma(ps, d2, SinD<1>::v);
+        s = __builtin_fma(ps * d2, d, d);
+        double pc = CosD<8>::v;
+        pc = __builtin_fma(pc, d2, CosD<7>::v);
+        pc = __builtin_fma(pc, d2, CosD<6>::v);
+        pc = __builtin_fma(pc, d2, CosD<5>::v);
+        pc = __builtin_fma(pc, d2, CosD<4>::v);
+        pc = __builtin_fma(pc, d2, CosD<3>::v);
+        pc = __builtin_fma(pc, d2, CosD<2>::v);
+        pc = __builtin_fma(pc, d2, CosD<1>::v);
+        c = __builtin_fma(pc, d2, 1.0);
     } else {
-        return a.contrast * s[0] * s[1] * s[2] * sincf(0.5f * qa * s[0]) * sincf(0.5f * qb * s[1])
-             * sincf(0.5f * qc * s[2]);
+        sincos(d, &s, &c);
     }
+}
+
+// sin, cos of (mean + d) from those of the mean (host, exact) and of d.
+__device__ __forceinline__ void rotate_by(double sm, double cm, double d, double& s, double& c)
+{
+    double sd, cd;
+    sincos_small(d, sd, cd);
+    s = __builtin_fma(sm, cd, cm * sd);
+    c = __builtin_fma(cm, cd, -sm * sd);
 }
 
 // Particle axes A = R x, B = R y, C = R z with R = Rz(phi) Ry(theta) Rz(Psi),
 // from the sines and cosines of (theta, phi, Psi).
 struct Trig3 {
-    float st, ct, sp, cp, ss, cs;
+    double st, ct, sp, cp, ss, cs;
 };
 
-__device__ __forceinline__ void particle_axes(const Trig3& g, float A[3], float B[3], float C[3])
+// Projections of Q on the particle axes (Eq. (6)); C only when WANT_AB is false.
+template <bool WANT_AB>
+__device__ __forceinline__ void project(const Trig3& g, const double qv[3], double& qa, double& qb,
+                                        double& qc)
 {
-    A[0] = g.cp * g.ct * g.cs - g.sp * g.ss;
-    A[1] = g.sp * g.ct * g.cs + g.cp * g.ss;
-    A[2] = -g.st * g.cs;
-    B[0] = -g.cp * g.ct * g.ss - g.sp * g.cs;
-    B[1] = -g.sp * g.ct * g.ss + g.cp * g.cs;
-    B[2] = g.st * g.ss;
-    C[0] = g.cp * g.st;
-    C[1] = g.sp * g.st;
-    C[2] = g.ct;
+    const double cx = g.cp * g.st, cy = g.sp * g.st, cz = g.ct;
+    qc = qv[0] * cx + qv[1] * cy + qv[2] * cz;
+    if constexpr (WANT_AB) {
+        const double ax = g.cp * g.ct * g.cs - g.sp * g.ss;
+        const double ay = g.sp * g.ct * g.cs + g.cp * g.ss;
+        const double az = -g.st * g.cs;
+        const double bx = -g.cp * g.ct * g.ss - g.sp * g.cs;
+        const double by = -g.sp * g.ct * g.ss + g.cp * g.cs;
+        const double bz = g.st * g.ss;
+        qa = qv[0] * ax + qv[1] * ay + qv[2] * az;
+        qb = qv[0] * bx + qv[1] * by + qv[2] * bz;
+    } else {
+        qa = qb = 0.0;
+    }
 }
 
-// sin and cos of (mean + d) from those of the mean (exact on the host) and of
-// the small offset d: keeps the rounding of the mean angle out of FP32.
-__device__ __forceinline__ void rotate_by(float sm, float cm, float d, float& s, float& c)
+// ---------------------------------------------------------------- models
+enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParallelepiped = 4 };
+
+// F of one drawn particle (MC mode).  y scales the sizes selected by the
+// polydispersity mask; q, qa, qb, qc are |Q| and its projections (FP64).
+template <int KIND>
+__device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, double q, double qa,
+                                              double qb, double qc)
 {
-    float sd, cd;
-    sincosf(d, &sd, &cd);
-    s = __builtin_fmaf(sm, cd, cm * sd);
-    c = __builtin_fmaf(cm, cd, -sm * sd);
+    double s[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[c] = (a.poly_mask >> c & 1) ? a.size[c] * y : a.size[c];
+    constexpr float k43pi = (float)(4.0 / 3.0 * kPi);
+    if constexpr (KIND == kSphere) {
+        const float r = (float)s[0];
+        return a.contrast * k43pi * r * r * r * sph3j_d(q * s[0]);
+    } else if constexpr (KIND == kCoreShell) {
+        const double ro_d = s[0] + a.shell;
+        const float rc = (float)s[0], ro = (float)ro_d;
+        return a.cs_core * k43pi * rc * rc * rc * sph3j_d(q * s[0])
+             + a.cs_shell * k43pi * ro * ro * ro * sph3j_d(q * ro_d);
+    } else if constexpr (KIND == kCylinder) {
+        const double qab = sqrt(fmax(__builtin_fma(q, q, -qc * qc), 0.0));
+        const float r = (float)s[0], len = (float)s[1];
+        return a.contrast * (float)kPi * r * r * len * sinc_d(0.5 * qc * s[1])
+             * lambda1_f((float)(qab * s[0]));
+    } else if constexpr (KIND == kEllipsoid) {
+        const double xa = qa * s[0], xb = qb * s[1], xc = qc * s[2];
+        const double x = sqrt(xa * xa + xb * xb + xc * xc);
+        return a.contrast * k43pi * (float)s[0] * (float)s[1] * (float)s[2] * sph3j_d(x);
+    } else {
+        return a.contrast * (float)s[0] * (float)s[1] * (float)s[2] * sinc_d(0.5 * qa * s[0])
+             * sinc_d(0.5 * qb * s[1]) * sinc_d(0.5 * qc * s[2]);
+    }
+}
+
+// F in FP32 throughout (quadrature loops; sizes s and projections FP32).
+template <int KIND>
+__device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3], float q, float qa,
+                                             float qb, float qc)
+{
+    constexpr float k43pi = (float)(4.0 / 3.0 * kPi);
+    if constexpr (KIND == kSphere) {
+        const float r = s[0];
+        return a.contrast * k43pi * r * r * r * sph3j_f(q * r);
+    } else if constexpr (KIND == kCoreShell) {
+        const float rc = s[0], ro = s[0] + a.fshell;
+        return a.cs_core * k43pi * rc * rc * rc * sph3j_f(q * rc)
+             + a.cs_shell * k43pi * ro * ro * ro * sph3j_f(q * ro);
+    } else if constexpr (KIND == kCylinder) {
+        const float r = s[0], len = s[1];
+        const float qab = sqrtf(fmaxf(__builtin_fmaf(q, q, -qc * qc), 0.0f));
+        return a.contrast * (float)kPi * r * r * len * sinc_f(0.5f * qc * len) * lambda1_f(qab * r);
+    } else if constexpr (KIND == kEllipsoid) {
+        const float xa = qa * s[0], xb = qb * s[1], xc = qc * s[2];
+        const float x = sqrtf(xa * xa + xb * xb + xc * xc);
+        return a.contrast * k43pi * s[0] * s[1] * s[2] * sph3j_f(x);
+    } else {
+        return a.contrast * s[0] * s[1] * s[2] * sinc_f(0.5f * qa * s[0]) * sinc_f(0.5f * qb * s[1])
+             * sinc_f(0.5f * qc * s[2]);
+    }
+}
+
+// ---------------------------------------------------------------- exact average
+// <F^2>(q) over the Schulz size nodes and (isotropic) the orientation nodes
+// held in LDS: lq = mu[n] wmu[n] cb[n] sb[n] wb[n] y[ny] wy[ny].
+template <int KIND>
+__device__ __forceinline__ float quad_average(const TraceArgs& a, const float* lq, float q,
+                                              const float qv[3])
+{
+    const int n = a.quad_n, ny = a.quad_ny;
+    const float* mu = lq;
+    const float* wmu = lq + n;
+    const float* cb = lq + 2 * n;
+    const float* sb = lq + 3 * n;
+    const float* wb = lq + 4 * n;
+    const float* ys = lq + 5 * n;
+    const float* wy = lq + 5 * n + ny;
+    float qa0 = 0.0f, qb0 = 0.0f, qc0 = 0.0f;
+    if (a.quad_dims == 0 && KIND >= kCylinder) {
+        qa0 = qv[0] * a.fA[0] + qv[1] * a.fA[1] + qv[2] * a.fA[2];
+        qb0 = qv[0] * a.fB[0] + qv[1] * a.fB[1] + qv[2] * a.fB[2];
+        qc0 = qv[0] * a.fC[0] + qv[1] * a.fC[1] + qv[2] * a.fC[2];
+    }
+    float total = 0.0f;
+    for (int j = 0; j < ny; ++j) {
+        const float y = ys[j];
+        float s[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s[c] = (a.poly_mask >> c & 1) ? a.fsize[c] * y : a.fsize[c];
+        float avg = 0.0f;
+        if (a.quad_dims == 0) {
+            const float f = amplitude_f<KIND>(a, s, q, qa0, qb0, qc0);
+            avg = f * f;
+        } else if (a.quad_dims == 1) {
+            for (int i = 0; i < n; ++i) {
+                const float m = mu[i];
+                const float st = sqrtf(fmaxf(1.0f - m * m, 0.0f));
+                const float f = amplitude_f<KIND>(a, s, q, q * st, 0.0f, q * m);
+                avg = __builtin_fmaf(wmu[i], f * f, avg);
+            }
+        } else {
+            for (int i = 0; i < n; ++i) {
+                const float m = mu[i];
+                const float qst = q * sqrtf(fmaxf(1.0f - m * m, 0.0f));
+                const float qc = q * m;
+                float inner = 0.0f;
+                for (int l = 0; l < n; ++l) {
+                    const float f = amplitude_f<KIND>(a, s, q, qst * cb[l], qst * sb[l], qc);
+                    inner = __builtin_fmaf(wb[l], f * f, inner);
+                }
+                avg = __builtin_fmaf(wmu[i], inner, avg);
+            }
+        }
+        total = __builtin_fmaf(wy[j], avg, total);
+    }
+    return total;
 }
 
 // ---------------------------------------------------------------- one neutron
@@ -287,17 +503,11 @@ struct Event {
     float q;        // 0 when the sample is missed
 };
 
-// Exact average <F^2>(q) over the Schulz size nodes and (isotropic) the
-// orientation nodes held in LDS.
-template <int KIND>
-__device__ __forceinline__ float quad_average(const TraceArgs& a, const float* lq, float q,
-                                              const float qv[3]);
-
 // Traces neutron i.  tab_size/tab_norm point to the LDS copies of the
 // tables; lq to the LDS copy of the quadrature nodes (QUAD mode).
 template <int KIND, int MODE>
 __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
-                                               const float* tab_size, const float* tab_norm,
+                                               const double* tab_size, const double* tab_norm,
                                                const float* lq)
 {
     Event ev{-1, 0.0f, 0.0f};
@@ -364,58 +574,50 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     const double fyp = floor((yd + a.det_hh) * a.inv_py);
     const bool on_det = fxp >= 0.0 && fxp < (double)a.nx && fyp >= 0.0 && fyp < (double)a.ny;
 
-    // the weight (computed for every lane: the wave runs it anyway)
-    float qv[3];
+    // scattering vector in the lab frame (anisotropic models)
+    double qvd[3] = {0.0, 0.0, 0.0};
     if constexpr (KIND >= kCylinder) {
-        qv[0] = (float)(k * __builtin_fma(s2, px, -t * kx));
-        qv[1] = (float)(k * __builtin_fma(s2, py, -t * ky));
-        qv[2] = (float)(k * __builtin_fma(s2, pz, -t * kz));
+        qvd[0] = k * __builtin_fma(s2, px, -t * kx);
+        qvd[1] = k * __builtin_fma(s2, py, -t * ky);
+        qvd[2] = k * __builtin_fma(s2, pz, -t * kz);
     }
+    // the weight (computed for every lane: the wave runs it anyway)
     float f2;
     if constexpr (MODE == 0) {
-        float y = 1.0f;
+        double y = 1.0;
         Trig3 g{a.ang_sin[0], a.ang_cos[0], a.ang_sin[1], a.ang_cos[1], a.ang_sin[2], a.ang_cos[2]};
         if (a.third_block) {
             const U4 r2 = philox4x32_10(ilo, ihi, 2u, a.exp_id, a.seed_lo, a.seed_hi);
-            if (a.poly_on) y = fmaxf(table_lerp(tab_size, a.M, u32f(r2.x)), 0.0f);
+            if (a.poly_on) y = fmax(table_lerp(tab_size, a.M, u64(r2.x)), 0.0);
             if constexpr (KIND >= kCylinder) {
                 if (a.orient_kind == 1) {
                     rotate_by(a.ang_sin[0], a.ang_cos[0],
-                              a.ang_sigma[0] * table_lerp(tab_norm, a.M, u32f(r2.y)), g.st, g.ct);
+                              a.ang_sigma[0] * table_lerp(tab_norm, a.M, u64(r2.y)), g.st, g.ct);
                     rotate_by(a.ang_sin[1], a.ang_cos[1],
-                              a.ang_sigma[1] * table_lerp(tab_norm, a.M, u32f(r2.z)), g.sp, g.cp);
-                    rotate_by(a.ang_sin[2], a.ang_cos[2],
-                              a.ang_sigma[2] * table_lerp(tab_norm, a.M, u32f(r2.w)), g.ss, g.cs);
+                              a.ang_sigma[1] * table_lerp(tab_norm, a.M, u64(r2.z)), g.sp, g.cp);
+                    if constexpr (KIND != kCylinder)
+                        rotate_by(a.ang_sin[2], a.ang_cos[2],
+                                  a.ang_sigma[2] * table_lerp(tab_norm, a.M, u64(r2.w)), g.ss, g.cs);
                 } else if (a.orient_kind == 2) {
                     // cos(theta) uniform in [-1, 1]; phi, Psi uniform in [0, 2 pi)
-                    g.ct = __builtin_fmaf(2.0f, u32f(r2.y), -1.0f);
-                    g.st = sqrtf(fmaxf(__builtin_fmaf(-g.ct, g.ct, 1.0f), 0.0f));
-                    sincospif(2.0f * u32f(r2.z), &g.sp, &g.cp);
-                    sincospif(2.0f * u32f(r2.w), &g.ss, &g.cs);
+                    g.ct = __builtin_fma(2.0, u64(r2.y), -1.0);
+                    g.st = sqrt(fmax(__builtin_fma(-g.ct, g.ct, 1.0), 0.0));
+                    sincospi(2.0 * u64(r2.z), &g.sp, &g.cp);
+                    if constexpr (KIND != kCylinder) sincospi(2.0 * u64(r2.w), &g.ss, &g.cs);
                 } else if (a.orient_kind == 3) {
                     // the literal rule: theta uniform in [0, pi)
-                    sincospif(u32f(r2.y), &g.st, &g.ct);
-                    sincospif(2.0f * u32f(r2.z), &g.sp, &g.cp);
-                    sincospif(2.0f * u32f(r2.w), &g.ss, &g.cs);
+                    sincospi(u64(r2.y), &g.st, &g.ct);
+                    sincospi(2.0 * u64(r2.z), &g.sp, &g.cp);
+                    if constexpr (KIND != kCylinder) sincospi(2.0 * u64(r2.w), &g.ss, &g.cs);
                 }
             }
         }
-        float s[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) s[c] = (a.poly_mask >> c & 1) ? a.size[c] * y : a.size[c];
-        float qa = 0.0f, qb = 0.0f, qc = 0.0f;
-        if constexpr (KIND >= kCylinder) {
-            float A[3], B[3], C[3];
-            particle_axes(g, A, B, C);
-            qc = qv[0] * C[0] + qv[1] * C[1] + qv[2] * C[2];
-            if constexpr (KIND != kCylinder) {
-                qa = qv[0] * A[0] + qv[1] * A[1] + qv[2] * A[2];
-                qb = qv[0] * B[0] + qv[1] * B[1] + qv[2] * B[2];
-            }
-        }
-        const float f = amplitude<KIND>(a, s, q, qa, qb, qc);
+        double qa = 0.0, qb = 0.0, qc = 0.0;
+        if constexpr (KIND >= kCylinder) project<KIND != kCylinder>(g, qvd, qa, qb, qc);
+        const float f = amplitude_mc<KIND>(a, y, qd, qa, qb, qc);
         f2 = f * f;
     } else {
+        const float qv[3] = {(float)qvd[0], (float)qvd[1], (float)qvd[2]};
         f2 = quad_average<KIND>(a, lq, q, qv);
     }
     float w = (float)(len * a.wscale) * f2;
@@ -425,65 +627,6 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
         ev.w = w;
     }
     return ev;
-}
-
-// LDS layout of the quadrature nodes: mu[n], wmu[n], cb[n], sb[n], wb[n],
-// y[ny], wy[ny].
-template <int KIND>
-__device__ __forceinline__ float quad_average(const TraceArgs& a, const float* lq, float q,
-                                              const float qv[3])
-{
-    const int n = a.quad_n, ny = a.quad_ny;
-    const float* mu = lq;
-    const float* wmu = lq + n;
-    const float* cb = lq + 2 * n;
-    const float* sb = lq + 3 * n;
-    const float* wb = lq + 4 * n;
-    const float* ys = lq + 5 * n;
-    const float* wy = lq + 5 * n + ny;
-    float total = 0.0f;
-    for (int j = 0; j < ny; ++j) {
-        const float y = ys[j];
-        float s[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) s[c] = (a.poly_mask >> c & 1) ? a.size[c] * y : a.size[c];
-        float avg = 0.0f;
-        if (a.quad_dims == 0) {
-            float qa = 0.0f, qb = 0.0f, qc = 0.0f;
-            if constexpr (KIND >= kCylinder) {
-                float A[3], B[3], C[3];
-                const Trig3 g{a.ang_sin[0], a.ang_cos[0], a.ang_sin[1], a.ang_cos[1], a.ang_sin[2],
-                              a.ang_cos[2]};
-                particle_axes(g, A, B, C);
-                qa = qv[0] * A[0] + qv[1] * A[1] + qv[2] * A[2];
-                qb = qv[0] * B[0] + qv[1] * B[1] + qv[2] * B[2];
-                qc = qv[0] * C[0] + qv[1] * C[1] + qv[2] * C[2];
-            }
-            const float f = amplitude<KIND>(a, s, q, qa, qb, qc);
-            avg = f * f;
-        } else if (a.quad_dims == 1) {
-            for (int i = 0; i < n; ++i) {
-                const float m = mu[i];
-                const float st = sqrtf(fmaxf(1.0f - m * m, 0.0f));
-                const float f = amplitude<KIND>(a, s, q, q * st, 0.0f, q * m);
-                avg = __builtin_fmaf(wmu[i], f * f, avg);
-            }
-        } else {
-            for (int i = 0; i < n; ++i) {
-                const float m = mu[i];
-                const float qst = q * sqrtf(fmaxf(1.0f - m * m, 0.0f));
-                const float qc = q * m;
-                float inner = 0.0f;
-                for (int l = 0; l < n; ++l) {
-                    const float f = amplitude<KIND>(a, s, q, qst * cb[l], qst * sb[l], qc);
-                    inner = __builtin_fmaf(wb[l], f * f, inner);
-                }
-                avg = __builtin_fmaf(wmu[i], inner, avg);
-            }
-        }
-        total = __builtin_fmaf(wy[j], avg, total);
-    }
-    return total;
 }
 
 }  // namespace sans

@@ -48,16 +48,36 @@ int fail(int status, const std::string& msg)
 
 // ------------------------------------------------------------------ kernels
 
-// Stage a float array into LDS with all threads of the block.
-__device__ __forceinline__ void stage(float* dst, const float* src, int n)
+// Stage an array into LDS with all threads of the block.
+template <typename T>
+__device__ __forceinline__ void stage(T* dst, const T* src, int n)
 {
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
-// Dynamic LDS: [hist (LDS tally only)] [size table] [normal table] [quad nodes]
+// Dynamic LDS, in doubles: [hist (LDS tally only)] [size table] [normal table]
+// [quadrature nodes (floats)]
 struct LdsLayout {
-    int hist_doubles, tab_size_off, tab_norm_off, quad_off, total_floats;
+    int hist, tab_size, tab_norm, quad, total;  // offsets / total in doubles
+    int quad_floats;
 };
+
+struct LdsPtrs {
+    double* hist;
+    double* tsize;
+    double* tnorm;
+    float* lq;
+};
+
+__device__ __forceinline__ LdsPtrs stage_all(const TraceArgs& a, const LdsLayout& lay, double* lds)
+{
+    LdsPtrs p{lds + lay.hist, lds + lay.tab_size, lds + lay.tab_norm,
+              reinterpret_cast<float*>(lds + lay.quad)};
+    if (a.tab_size) stage(p.tsize, a.tab_size, a.M);
+    if (a.tab_norm) stage(p.tnorm, a.tab_norm, a.M);
+    if (lay.quad_floats) stage(p.lq, a.quad_nodes, lay.quad_floats);
+    return p;
+}
 
 template <int KIND, int MODE, int TALLY>
 __global__ __launch_bounds__(kBlock) void k_trace(const TraceArgs a, LdsLayout lay, double* det,
@@ -65,24 +85,10 @@ __global__ __launch_bounds__(kBlock) void k_trace(const TraceArgs a, LdsLayout l
                                                   double* replicas)
 {
     extern __shared__ double lds_d[];
-    float* lds_f = reinterpret_cast<float*>(lds_d + lay.hist_doubles);
-    float* tsize = lds_f + lay.tab_size_off;
-    float* tnorm = lds_f + lay.tab_norm_off;
-    float* lq = lds_f + lay.quad_off;
-    if (a.tab_size) stage(tsize, a.tab_size, a.M);
-    if (a.tab_norm) stage(tnorm, a.tab_norm, a.M);
-    if constexpr (MODE == 1) {
-        stage(lq, a.quad_mu, a.quad_n);
-        stage(lq + a.quad_n, a.quad_wmu, a.quad_n);
-        stage(lq + 2 * a.quad_n, a.quad_cb, a.quad_n);
-        stage(lq + 3 * a.quad_n, a.quad_sb, a.quad_n);
-        stage(lq + 4 * a.quad_n, a.quad_wb, a.quad_n);
-        stage(lq + 5 * a.quad_n, a.quad_y, a.quad_ny);
-        stage(lq + 5 * a.quad_n + a.quad_ny, a.quad_wy, a.quad_ny);
-    }
+    const LdsPtrs lp = stage_all(a, lay, lds_d);
     const int npix = a.nx * a.ny;
     if constexpr (TALLY == SANS_TALLY_LDS) {
-        for (int i = threadIdx.x; i < npix; i += blockDim.x) lds_d[i] = 0.0;
+        for (int i = threadIdx.x; i < npix; i += blockDim.x) lp.hist[i] = 0.0;
     }
     __syncthreads();
 
@@ -93,11 +99,11 @@ __global__ __launch_bounds__(kBlock) void k_trace(const TraceArgs a, LdsLayout l
     }
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += stride) {
-        const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, tsize, tnorm, lq);
+        const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
         if (ev.pixel >= 0) {
             const double w = (double)ev.w;
             if constexpr (TALLY == SANS_TALLY_LDS) {
-                __hip_atomic_fetch_add(lds_d + ev.pixel, w, __ATOMIC_RELAXED,
+                __hip_atomic_fetch_add(lp.hist + ev.pixel, w, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
             } else {
                 __hip_atomic_fetch_add(target + ev.pixel, w, __ATOMIC_RELAXED,
@@ -114,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const TraceArgs a, LdsLayout l
     if constexpr (TALLY == SANS_TALLY_LDS) {
         __syncthreads();
         for (int i = threadIdx.x; i < npix; i += blockDim.x) {
-            const double v = lds_d[i];
+            const double v = lp.hist[i];
             if (v != 0.0)
                 __hip_atomic_fetch_add(det + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -126,25 +132,11 @@ __global__ __launch_bounds__(kBlock) void k_debug(const TraceArgs a, LdsLayout l
                                                   float* w, float* q)
 {
     extern __shared__ double lds_d[];
-    float* lds_f = reinterpret_cast<float*>(lds_d);
-    float* tsize = lds_f + lay.tab_size_off;
-    float* tnorm = lds_f + lay.tab_norm_off;
-    float* lq = lds_f + lay.quad_off;
-    if (a.tab_size) stage(tsize, a.tab_size, a.M);
-    if (a.tab_norm) stage(tnorm, a.tab_norm, a.M);
-    if constexpr (MODE == 1) {
-        stage(lq, a.quad_mu, a.quad_n);
-        stage(lq + a.quad_n, a.quad_wmu, a.quad_n);
-        stage(lq + 2 * a.quad_n, a.quad_cb, a.quad_n);
-        stage(lq + 3 * a.quad_n, a.quad_sb, a.quad_n);
-        stage(lq + 4 * a.quad_n, a.quad_wb, a.quad_n);
-        stage(lq + 5 * a.quad_n, a.quad_y, a.quad_ny);
-        stage(lq + 5 * a.quad_n + a.quad_ny, a.quad_wy, a.quad_ny);
-    }
+    const LdsPtrs lp = stage_all(a, lay, lds_d);
     __syncthreads();
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.n) return;
-    const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, tsize, tnorm, lq);
+    const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
     if (pixel) pixel[j] = ev.pixel;
     if (w) w[j] = ev.w;
     if (q) q[j] = ev.q;
@@ -197,14 +189,8 @@ __global__ __launch_bounds__(kBlock) void k_pq_avg(const TraceArgs a, LdsLayout 
                                                    const float* qvec, int64_t n, float* out)
 {
     extern __shared__ double lds_d[];
-    float* lq = reinterpret_cast<float*>(lds_d) + lay.quad_off;
-    stage(lq, a.quad_mu, a.quad_n);
-    stage(lq + a.quad_n, a.quad_wmu, a.quad_n);
-    stage(lq + 2 * a.quad_n, a.quad_cb, a.quad_n);
-    stage(lq + 3 * a.quad_n, a.quad_sb, a.quad_n);
-    stage(lq + 4 * a.quad_n, a.quad_wb, a.quad_n);
-    stage(lq + 5 * a.quad_n, a.quad_y, a.quad_ny);
-    stage(lq + 5 * a.quad_n + a.quad_ny, a.quad_wy, a.quad_ny);
+    const LdsPtrs lp = stage_all(a, lay, lds_d);
+    float* lq = lp.lq;
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
@@ -281,9 +267,10 @@ struct sans_model_s {
     sans_params p;
     TraceArgs args;            // constants; per-call fields are filled at launch
     double mean_v = 0.0, wscale = 0.0, omc = 0.0;
-    std::vector<float> h_tab_size, h_tab_norm, h_quad;
-    float* d_tab_size = nullptr;
-    float* d_tab_norm = nullptr;
+    std::vector<double> h_tab_size, h_tab_norm;
+    std::vector<float> h_quad;
+    double* d_tab_size = nullptr;
+    double* d_tab_norm = nullptr;
     float* d_quad = nullptr;
     double* d_replicas = nullptr;
     size_t replica_pix = 0;
@@ -384,12 +371,27 @@ int configure(sans_model_s* m, const sans_params* p)
     m->wscale = 1e10 * dOmega * p->phi / m->mean_v;
     a.wscale = m->wscale;
     for (int k = 0; k < 3; ++k) {
-        a.size[k] = (float)p->size[k];
-        a.ang_sin[k] = (float)std::sin(p->orient_mean[k]);
-        a.ang_cos[k] = (float)std::cos(p->orient_mean[k]);
-        a.ang_sigma[k] = (float)p->orient_sigma[k];
+        a.size[k] = p->size[k];
+        a.fsize[k] = (float)p->size[k];
+        a.ang_sin[k] = std::sin(p->orient_mean[k]);
+        a.ang_cos[k] = std::cos(p->orient_mean[k]);
+        a.ang_sigma[k] = p->orient_sigma[k];
     }
-    a.shell = (float)p->shell;
+    a.shell = p->shell;
+    a.fshell = (float)p->shell;
+    {
+        // fixed-orientation axes for the quadrature path: A = R x, B = R y, C = R z
+        const double st = a.ang_sin[0], ct = a.ang_cos[0], sp = a.ang_sin[1], cp = a.ang_cos[1],
+                     ss = a.ang_sin[2], cs = a.ang_cos[2];
+        const double A[3] = {cp * ct * cs - sp * ss, sp * ct * cs + cp * ss, -st * cs};
+        const double B[3] = {-cp * ct * ss - sp * cs, -sp * ct * ss + cp * cs, st * ss};
+        const double Cc[3] = {cp * st, sp * st, ct};
+        for (int k = 0; k < 3; ++k) {
+            a.fA[k] = (float)A[k];
+            a.fB[k] = (float)B[k];
+            a.fC[k] = (float)Cc[k];
+        }
+    }
     a.contrast = (float)(p->sld[0] - p->sld[2]);
     a.cs_core = (float)(p->sld[0] - p->sld[1]);
     a.cs_shell = (float)(p->sld[1] - p->sld[2]);
@@ -419,13 +421,12 @@ int configure(sans_model_s* m, const sans_params* p)
     const bool norm_same = !first && old.table_size == p->table_size && !m->h_tab_norm.empty();
     if (need_size) {
         if (!size_same) {
-            std::vector<double> t(p->table_size);
-            host::schulz_table(p->poly, p->table_size, t.data());
-            m->h_tab_size.assign(t.begin(), t.end());
+            m->h_tab_size.assign(p->table_size, 0.0);
+            host::schulz_table(p->poly, p->table_size, m->h_tab_size.data());
             if (m->d_tab_size) HIP_TRY(hipFree(m->d_tab_size));
             m->d_tab_size = nullptr;
-            HIP_TRY(hipMalloc(&m->d_tab_size, sizeof(float) * p->table_size));
-            HIP_TRY(hipMemcpy(m->d_tab_size, m->h_tab_size.data(), sizeof(float) * p->table_size,
+            HIP_TRY(hipMalloc(&m->d_tab_size, sizeof(double) * p->table_size));
+            HIP_TRY(hipMemcpy(m->d_tab_size, m->h_tab_size.data(), sizeof(double) * p->table_size,
                               hipMemcpyHostToDevice));
         }
         a.tab_size = m->d_tab_size;
@@ -434,11 +435,11 @@ int configure(sans_model_s* m, const sans_params* p)
         if (!norm_same) {
             m->h_tab_norm.resize(p->table_size);
             for (int k = 0; k < p->table_size; ++k)
-                m->h_tab_norm[k] = (float)host::normal_quantile((k + 0.5) / p->table_size);
+                m->h_tab_norm[k] = host::normal_quantile((k + 0.5) / p->table_size);
             if (m->d_tab_norm) HIP_TRY(hipFree(m->d_tab_norm));
             m->d_tab_norm = nullptr;
-            HIP_TRY(hipMalloc(&m->d_tab_norm, sizeof(float) * p->table_size));
-            HIP_TRY(hipMemcpy(m->d_tab_norm, m->h_tab_norm.data(), sizeof(float) * p->table_size,
+            HIP_TRY(hipMalloc(&m->d_tab_norm, sizeof(double) * p->table_size));
+            HIP_TRY(hipMemcpy(m->d_tab_norm, m->h_tab_norm.data(), sizeof(double) * p->table_size,
                               hipMemcpyHostToDevice));
         }
         a.tab_norm = m->d_tab_norm;
@@ -497,13 +498,7 @@ int configure(sans_model_s* m, const sans_params* p)
         HIP_TRY(hipMalloc(&m->d_quad, sizeof(float) * m->h_quad.size()));
         HIP_TRY(hipMemcpy(m->d_quad, m->h_quad.data(), sizeof(float) * m->h_quad.size(),
                           hipMemcpyHostToDevice));
-        a.quad_mu = m->d_quad;
-        a.quad_wmu = m->d_quad + n;
-        a.quad_cb = m->d_quad + 2 * n;
-        a.quad_sb = m->d_quad + 3 * n;
-        a.quad_wb = m->d_quad + 4 * n;
-        a.quad_y = m->d_quad + 5 * n;
-        a.quad_wy = m->d_quad + 5 * n + ny;
+        a.quad_nodes = m->d_quad;
     }
     return SANS_OK;
 }
@@ -512,19 +507,21 @@ LdsLayout layout(const sans_model_s* m, bool hist)
 {
     LdsLayout l{};
     const TraceArgs& a = m->args;
-    l.hist_doubles = hist ? a.nx * a.ny : 0;
     int off = 0;
-    l.tab_size_off = off;
+    l.hist = off;
+    if (hist) off += a.nx * a.ny;
+    l.tab_size = off;
     if (a.tab_size) off += a.M;
-    l.tab_norm_off = off;
+    l.tab_norm = off;
     if (a.tab_norm) off += a.M;
-    l.quad_off = off;
-    if (m->p.mode == SANS_MODE_QUAD) off += 5 * a.quad_n + 2 * a.quad_ny;
-    l.total_floats = off;
+    l.quad = off;
+    l.quad_floats = (m->p.mode == SANS_MODE_QUAD) ? 5 * a.quad_n + 2 * a.quad_ny : 0;
+    off += (l.quad_floats + 1) / 2;
+    l.total = off;
     return l;
 }
 
-size_t lds_bytes(const LdsLayout& l) { return sizeof(double) * l.hist_doubles + sizeof(float) * l.total_floats; }
+size_t lds_bytes(const LdsLayout& l) { return sizeof(double) * l.total; }
 
 int choose_tally(const sans_model_s* m)
 {
@@ -721,13 +718,13 @@ int sans_debug_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t n_bloc
     return SANS_OK;
 }
 
-int sans_debug_table(sans_model_t m, int32_t which, float* out, int32_t n)
+int sans_debug_table(sans_model_t m, int32_t which, double* out, int32_t n)
 {
     if (!m || !out) return fail(SANS_E_INVALID_ARG, "NULL argument");
-    const std::vector<float>& t = which == 0 ? m->h_tab_norm : m->h_tab_size;
+    const std::vector<double>& t = which == 0 ? m->h_tab_norm : m->h_tab_size;
     if (which < 0 || which > 1 || t.empty()) return fail(SANS_E_UNSUPPORTED, "no such table");
     if (n != (int32_t)t.size()) return fail(SANS_E_INVALID_ARG, "n must equal table_size");
-    std::memcpy(out, t.data(), sizeof(float) * n);
+    std::memcpy(out, t.data(), sizeof(double) * n);
     return SANS_OK;
 }
 

@@ -66,7 +66,7 @@ def _load():
     L.sans_trace_ex.argtypes = [vp, u64, u64, u64, u32, u32, vp, vp, vp, vp]
     L.sans_debug_trace.argtypes = [vp, u64, u64, u64, u32, vp, vp, vp, vp]
     L.sans_debug_philox.argtypes = [u64, u64, u64, u32, u32, vp, vp]
-    L.sans_debug_table.argtypes = [vp, i32, P(C.c_float), i32]
+    L.sans_debug_table.argtypes = [vp, i32, P(C.c_double), i32]
     L.sans_pq_avg.argtypes = [vp, vp, vp, i64, vp, vp]
     L.sans_model_constants.argtypes = [vp, P(C.c_double)]
     L.sans_abi_params_size.restype = u32
@@ -177,8 +177,8 @@ def sans_debug_philox(seed: int, first: int, n: int, n_blocks: int, exp_id: int,
 
 def sans_debug_table(h, which: int, n: int):
     import numpy as np
-    out = np.zeros(n, dtype=np.float32)
-    _check(lib.sans_debug_table(h, which, out.ctypes.data_as(C.POINTER(C.c_float)), n),
+    out = np.zeros(n, dtype=np.float64)
+    _check(lib.sans_debug_table(h, which, out.ctypes.data_as(C.POINTER(C.c_double)), n),
            "sans_debug_table")
     return out
 

@@ -85,8 +85,8 @@ def test_tables_match_oracle(S, poly):
     ts = S.sans_debug_table(m.handle, 1, M)
     on = oracle.table_normal(M)
     os_ = oracle.table_schulz(M, poly)
-    assert np.allclose(tn, on, rtol=2e-7, atol=1e-7)
-    assert np.allclose(ts, os_, rtol=2e-7, atol=1e-9)
+    assert np.allclose(tn, on, rtol=1e-12, atol=1e-13)
+    assert np.allclose(ts, os_, rtol=1e-12, atol=1e-14)
     m.close()
 
 
