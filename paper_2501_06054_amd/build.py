@@ -25,6 +25,10 @@ FLAGS = [
     "-munsafe-fp-atomics",
     # no packed FP32 (v_pk_*_f32) code generation
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep constant materialisation inside the neutron loops: hoisting it out
+    # (machine LICM) keeps dozens of FP64 constants live in VGPRs and halves
+    # the waves per SIMD of the grid-stride trace kernels
+    "-mllvm", "-disable-machine-licm",
     "-Wno-unused-command-line-argument",
     "-Wl,-rpath,/opt/rocm/lib",
 ]

@@ -542,8 +542,10 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
             }
         }
     }
-    if (!(s_out > s_in)) return ev;
-    const double len = s_out - s_in;
+    // no early exit: a miss is carried as a flag (straight-line loop bodies
+    // keep far fewer registers live than branchy ones)
+    const bool in_sample = s_out > s_in;
+    const double len = in_sample ? s_out - s_in : 0.0;
     const double sp = __builtin_fma(u64(r1.y), len, s_in);
     const double rx = __builtin_fma(sp, kx, sx), ry = __builtin_fma(sp, ky, sy),
                  rz = __builtin_fma(sp, kz, a.src_z);
@@ -563,15 +565,16 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     const double fx = c2 * kx + s2 * px, fy = c2 * ky + s2 * py, fz = c2 * kz + s2 * pz;
     const double qd = k * sqrt(2.0 * t);
     const float q = (float)qd;
-    ev.q = q;
+    ev.q = in_sample ? q : 0.0f;
 
     // detector plane and pixel
-    if (!(fz > 0.0)) return ev;
+    const bool forward = fz > 0.0;
     const double sd = (a.det_z - rz) / fz;
     const double xd = __builtin_fma(sd, fx, rx), yd = __builtin_fma(sd, fy, ry);
     const double fxp = floor((xd + a.det_hw) * a.inv_px);
     const double fyp = floor((yd + a.det_hh) * a.inv_py);
-    const bool on_det = fxp >= 0.0 && fxp < (double)a.nx && fyp >= 0.0 && fyp < (double)a.ny;
+    const bool on_det = in_sample && forward && fxp >= 0.0 && fxp < (double)a.nx && fyp >= 0.0
+                        && fyp < (double)a.ny;
 
     // scattering vector in the lab frame (anisotropic models)
     double qvd[3] = {0.0, 0.0, 0.0};
