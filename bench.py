@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="coreshell_py")
     ap.add_argument("--n", type=float, default=None, help="neutrons per step (default: workload's)")
-    ap.add_argument("--tally", default="auto", choices=["auto", "global", "lds", "xcd"])
+    ap.add_argument("--tally", default="auto", choices=["auto", "global", "lds", "xcd", "binned"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample (0 = skip)")
     return ap.parse_args()

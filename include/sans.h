@@ -88,12 +88,19 @@ typedef enum {
                                        phi, Psi ~ U[0,2pi] (not isotropic)       */
 } sans_orient;
 
-/* Tally strategies (all give the same detector up to FP64 summation order). */
+/* Tally strategies (all give the same detector up to FP64 summation order).
+ * AUTO takes LDS when the whole detector (plus the tables) fits in a
+ * workgroup's 160 KiB of LDS, else BINNED.  Requests for det_w2/det_count use
+ * the atomic path (GLOBAL, or XCD when asked for). */
 typedef enum {
-    SANS_TALLY_AUTO = 0,   /* library choice (tuned)                            */
-    SANS_TALLY_GLOBAL = 1, /* one FP64 global atomic per detected neutron        */
-    SANS_TALLY_LDS = 2,    /* workgroup-private FP64 histogram in LDS, flushed   */
-    SANS_TALLY_XCD = 3     /* one detector replica per XCD, summed at the end     */
+    SANS_TALLY_AUTO = 0,   /* library choice                                      */
+    SANS_TALLY_GLOBAL = 1, /* one FP64 global atomic per detected neutron          */
+    SANS_TALLY_LDS = 2,    /* workgroup-private FP64 histogram of the detector in
+                              LDS; partial histograms summed by a second kernel   */
+    SANS_TALLY_XCD = 3,    /* one detector replica per XCD, summed at the end      */
+    SANS_TALLY_BINNED = 4  /* two passes per chunk of neutrons: events sorted into
+                              row bands of the detector, then each band summed in
+                              LDS (detectors too large for LDS)                    */
 } sans_tally;
 
 /* Flags. */

@@ -1,8 +1,12 @@
 // sans_lib.hip -- kernels and C ABI of libsans (gfx950).
 //
 // Kernels
-//   k_trace<KIND, MODE, TALLY>  the hot path: one neutron per lane, grid-stride
-//                               over the neutron range, tally into the detector
+//   k_trace_hist<KIND, MODE>    the hot path for detectors that fit in LDS: one
+//                               neutron per lane, grid-stride over the range,
+//                               FP64 LDS histogram per workgroup
+//   k_emit<KIND, MODE> +        the hot path for larger detectors: events binned
+//   k_bin_accumulate            by detector row band, then summed band by band in LDS
+//   k_trace<KIND, MODE, TALLY>  atomic tallies (global / per-XCD replica)
 //   k_debug<KIND, MODE>         the same per-neutron code, writing (pixel, w, q)
 //   k_philox                    raw Philox words for stream tests
 //   k_fill, k_sum_replicas      detector clearing / XCD replica reduction
@@ -79,6 +83,8 @@ __device__ __forceinline__ LdsPtrs stage_all(const TraceArgs& a, const LdsLayout
     return p;
 }
 
+// Atomic tallies: one FP64 atomic per detected neutron into the detector
+// (GLOBAL) or into this XCD's replica of it (XCD).
 template <int KIND, int MODE, int TALLY>
 __global__ __launch_bounds__(kBlock) void k_trace(const TraceArgs a, LdsLayout lay, double* det,
                                                   double* det_w2, unsigned long long* det_cnt,
@@ -86,29 +92,18 @@ __global__ __launch_bounds__(kBlock) void k_trace(const TraceArgs a, LdsLayout l
 {
     extern __shared__ double lds_d[];
     const LdsPtrs lp = stage_all(a, lay, lds_d);
-    const int npix = a.nx * a.ny;
-    if constexpr (TALLY == SANS_TALLY_LDS) {
-        for (int i = threadIdx.x; i < npix; i += blockDim.x) lp.hist[i] = 0.0;
-    }
     __syncthreads();
-
     double* target = det;
     if constexpr (TALLY == SANS_TALLY_XCD) {
         const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kXcds - 1);
-        target = replicas + (size_t)xcc * npix;
+        target = replicas + (size_t)xcc * a.nx * a.ny;
     }
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += stride) {
         const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
         if (ev.pixel >= 0) {
             const double w = (double)ev.w;
-            if constexpr (TALLY == SANS_TALLY_LDS) {
-                __hip_atomic_fetch_add(lp.hist + ev.pixel, w, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-            } else {
-                __hip_atomic_fetch_add(target + ev.pixel, w, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            }
+            __hip_atomic_fetch_add(target + ev.pixel, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (det_w2)
                 __hip_atomic_fetch_add(det_w2 + ev.pixel, w * w, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -117,14 +112,123 @@ __global__ __launch_bounds__(kBlock) void k_trace(const TraceArgs a, LdsLayout l
                                        __HIP_MEMORY_SCOPE_AGENT);
         }
     }
-    if constexpr (TALLY == SANS_TALLY_LDS) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < npix; i += blockDim.x) {
-            const double v = lp.hist[i];
-            if (v != 0.0)
-                __hip_atomic_fetch_add(det + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+}
+
+// LDS tally: the whole detector as an FP64 histogram in LDS, 1024 lanes per
+// workgroup; each workgroup writes its histogram to its own partial slot
+// (plain stores), summed afterwards by k_reduce_partials.
+constexpr int kHistBlock = 1024;
+
+template <int KIND, int MODE>
+__global__ __launch_bounds__(kHistBlock) void k_trace_hist(const TraceArgs a, LdsLayout lay,
+                                                           double* partial)
+{
+    extern __shared__ double lds_d[];
+    const LdsPtrs lp = stage_all(a, lay, lds_d);
+    const int npix = a.nx * a.ny;
+    for (int i = threadIdx.x; i < npix; i += blockDim.x) lp.hist[i] = 0.0;
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += stride) {
+        const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
+        if (ev.pixel >= 0)
+            __hip_atomic_fetch_add(lp.hist + ev.pixel, (double)ev.w, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+    __syncthreads();
+    double* out = partial + (size_t)blockIdx.x * npix;
+    for (int i = threadIdx.x; i < npix; i += blockDim.x) out[i] = lp.hist[i];
+}
+
+// det[p] (+)= sum over g < G of partial[g][p]  (p < npix)
+__global__ void k_reduce_partials(double* det, const double* partial, int G, int npix, int accumulate)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += partial[(size_t)g * npix + p];
+    det[p] = accumulate ? det[p] + s : s;
+}
+
+// Binned tally, pass 1: the events of one chunk of neutrons go to the bucket
+// of their detector tile (rows [t*rows, (t+1)*rows)).  Space in a bucket is
+// reserved once per workgroup iteration (one integer atomic per tile), ranks
+// inside the workgroup come from LDS counters.  An event is (pixel within
+// the tile, FP32 weight bits).
+constexpr int kEmitBlock = 256;
+constexpr int kMaxTiles = 64;
+
+template <int KIND, int MODE>
+__global__ __launch_bounds__(kEmitBlock) void k_emit(const TraceArgs a, LdsLayout lay, uint2* buckets,
+                                                     unsigned* bucket_count, unsigned cap,
+                                                     int tile_pixels, int ntiles)
+{
+    extern __shared__ double lds_d[];
+    __shared__ unsigned cnt[kMaxTiles], base[kMaxTiles];
+    const LdsPtrs lp = stage_all(a, lay, lds_d);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < a.n; j0 += stride) {
+        if (threadIdx.x < ntiles) cnt[threadIdx.x] = 0u;
+        __syncthreads();
+        const uint64_t j = j0 + threadIdx.x;
+        int t = -1;
+        unsigned rank = 0, local = 0;
+        float w = 0.0f;
+        if (j < a.n) {
+            const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
+            if (ev.pixel >= 0) {
+                t = ev.pixel / tile_pixels;
+                local = (unsigned)(ev.pixel - t * tile_pixels);
+                w = ev.w;
+                rank = atomicAdd(&cnt[t], 1u);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < ntiles) {
+            const unsigned c = cnt[threadIdx.x];
+            base[threadIdx.x] = c ? atomicAdd(bucket_count + threadIdx.x, c) : 0u;
+        }
+        __syncthreads();
+        if (t >= 0) buckets[(size_t)t * cap + base[t] + rank] = make_uint2(local, __float_as_uint(w));
+    }
+}
+
+// Binned tally, pass 2: workgroup (t, s) accumulates slice s of bucket t in
+// an LDS histogram of tile t and adds it to its own partial slot.
+__global__ __launch_bounds__(kHistBlock) void k_bin_accumulate(const uint2* buckets,
+                                                               const unsigned* bucket_count,
+                                                               unsigned cap, int tile_pixels,
+                                                               int slices, double* partial)
+{
+    extern __shared__ double hist[];
+    const int t = blockIdx.x / slices, sl = blockIdx.x % slices;
+    for (int i = threadIdx.x; i < tile_pixels; i += blockDim.x) hist[i] = 0.0;
+    __syncthreads();
+    const unsigned nt = bucket_count[t];
+    const unsigned lo = (unsigned)((uint64_t)nt * sl / slices);
+    const unsigned hi = (unsigned)((uint64_t)nt * (sl + 1) / slices);
+    const uint2* b = buckets + (size_t)t * cap;
+    for (unsigned i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const uint2 e = b[i];
+        __hip_atomic_fetch_add(hist + e.x, (double)__uint_as_float(e.y), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+    double* out = partial + (size_t)blockIdx.x * tile_pixels;
+    for (int i = threadIdx.x; i < tile_pixels; i += blockDim.x) out[i] += hist[i];
+}
+
+// det[p] (+)= sum over the slices of tile t(p) of partial[t][s][p - t*tile]
+__global__ void k_reduce_binned(double* det, const double* partial, int tile_pixels, int slices,
+                                int npix, int accumulate)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const int t = p / tile_pixels, q = p - t * tile_pixels;
+    const double* src = partial + (size_t)t * slices * tile_pixels + q;
+    double s = 0.0;
+    for (int k = 0; k < slices; ++k) s += src[(size_t)k * tile_pixels];
+    det[p] = accumulate ? det[p] + s : s;
 }
 
 template <int KIND, int MODE>
@@ -162,6 +266,12 @@ __global__ void k_fill(double* p, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_fill_u32(unsigned* p, int n)
+{
+    const int i = threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
 __global__ void k_fill_u64(unsigned long long* p, size_t n)
@@ -211,8 +321,7 @@ using PqFn = void (*)(const TraceArgs, LdsLayout, const float*, const float*, in
 template <int K, int M>
 TraceFn trace_fn(int tally)
 {
-    return tally == SANS_TALLY_LDS ? (TraceFn)k_trace<K, M, SANS_TALLY_LDS>
-         : tally == SANS_TALLY_XCD ? (TraceFn)k_trace<K, M, SANS_TALLY_XCD>
+    return tally == SANS_TALLY_XCD ? (TraceFn)k_trace<K, M, SANS_TALLY_XCD>
                                    : (TraceFn)k_trace<K, M, SANS_TALLY_GLOBAL>;
 }
 
@@ -221,6 +330,41 @@ TraceFn pick_trace(int kind, int mode, int tally)
 #define SANS_CASE(K)                                                                       \
     case K:                                                                                \
         return mode == 0 ? trace_fn<K, 0>(tally) : trace_fn<K, 1>(tally);
+    switch (kind) {
+        SANS_CASE(0)
+        SANS_CASE(1)
+        SANS_CASE(2)
+        SANS_CASE(3)
+        SANS_CASE(4)
+    }
+#undef SANS_CASE
+    return nullptr;
+}
+
+using HistFn = void (*)(const TraceArgs, LdsLayout, double*);
+using EmitFn = void (*)(const TraceArgs, LdsLayout, uint2*, unsigned*, unsigned, int, int);
+
+HistFn pick_hist(int kind, int mode)
+{
+#define SANS_CASE(K)                                                                       \
+    case K:                                                                                \
+        return mode == 0 ? (HistFn)k_trace_hist<K, 0> : (HistFn)k_trace_hist<K, 1>;
+    switch (kind) {
+        SANS_CASE(0)
+        SANS_CASE(1)
+        SANS_CASE(2)
+        SANS_CASE(3)
+        SANS_CASE(4)
+    }
+#undef SANS_CASE
+    return nullptr;
+}
+
+EmitFn pick_emit(int kind, int mode)
+{
+#define SANS_CASE(K)                                                                       \
+    case K:                                                                                \
+        return mode == 0 ? (EmitFn)k_emit<K, 0> : (EmitFn)k_emit<K, 1>;
     switch (kind) {
         SANS_CASE(0)
         SANS_CASE(1)
@@ -274,6 +418,12 @@ struct sans_model_s {
     float* d_quad = nullptr;
     double* d_replicas = nullptr;
     size_t replica_pix = 0;
+    // tally workspaces (grown on demand, freed with the model)
+    double* d_partial = nullptr;
+    size_t partial_cap = 0;     // doubles
+    uint2* d_buckets = nullptr;
+    size_t bucket_cap = 0;      // events
+    unsigned* d_bucket_count = nullptr;
     int device = 0;
     int num_cu = 256;
 };
@@ -291,7 +441,7 @@ int validate(const sans_params* p)
     if (p->mode == SANS_MODE_SURROGATE)
         return fail(SANS_E_UNSUPPORTED, "surrogate mode needs an attached network");
     if (p->orient_kind < 0 || p->orient_kind > 3) return fail(SANS_E_UNSUPPORTED, "unknown orientation kind");
-    if (p->tally < 0 || p->tally > 3) return fail(SANS_E_UNSUPPORTED, "unknown tally strategy");
+    if (p->tally < 0 || p->tally > 4) return fail(SANS_E_UNSUPPORTED, "unknown tally strategy");
     const int nsize = p->kind <= 1 ? 1 : (p->kind == 2 ? 2 : 3);
     for (int k = 0; k < nsize; ++k)
         if (!(p->size[k] > 0.0) || !finite(p->size[k])) return fail(SANS_E_INVALID_ARG, "size must be > 0");
@@ -523,14 +673,52 @@ LdsLayout layout(const sans_model_s* m, bool hist)
 
 size_t lds_bytes(const LdsLayout& l) { return sizeof(double) * l.total; }
 
-int choose_tally(const sans_model_s* m)
+// LDS budget of the histogram kernels' workgroups
+constexpr size_t kTileBytes = 128 * 1024;
+
+bool hist_fits(const sans_model_s* m)
 {
-    const int t = m->p.tally;
-    const LdsLayout l = layout(m, true);
-    const bool fits = lds_bytes(l) <= kLdsMax;
-    if (t == SANS_TALLY_LDS && !fits) return SANS_TALLY_GLOBAL;
-    if (t != SANS_TALLY_AUTO) return t;
-    return fits ? SANS_TALLY_LDS : SANS_TALLY_GLOBAL;
+    return lds_bytes(layout(m, true)) <= kLdsMax;
+}
+
+int choose_tally(const sans_model_s* m, bool extras)
+{
+    int t = m->p.tally;
+    // the optional sum-of-squares and count outputs use the atomic path
+    if (extras) return t == SANS_TALLY_XCD ? SANS_TALLY_XCD : SANS_TALLY_GLOBAL;
+    if (t == SANS_TALLY_AUTO) t = hist_fits(m) ? SANS_TALLY_LDS : SANS_TALLY_BINNED;
+    if (t == SANS_TALLY_LDS && !hist_fits(m)) t = SANS_TALLY_BINNED;
+    if (t == SANS_TALLY_BINNED) {
+        const size_t row_bytes = sizeof(double) * (size_t)m->p.nx;
+        const size_t rows = kTileBytes / row_bytes;
+        const size_t ntiles = rows ? ((size_t)m->p.ny + rows - 1) / rows : 0;
+        const size_t emit_lds = lds_bytes(layout(m, false)) + 2 * sizeof(unsigned) * kMaxTiles;
+        if (rows == 0 || ntiles > (size_t)kMaxTiles || emit_lds > kLdsMax) t = SANS_TALLY_GLOBAL;
+    }
+    return t;
+}
+
+// Grows a device workspace to at least `count` elements.
+template <typename T>
+int ensure(T*& ptr, size_t& cap, size_t count)
+{
+    if (cap >= count && ptr) return SANS_OK;
+    if (ptr) HIP_TRY(hipFree(ptr));
+    ptr = nullptr;
+    cap = 0;
+    if (hipMalloc(&ptr, sizeof(T) * count) != hipSuccess) {
+        ptr = nullptr;
+        return fail(SANS_E_NOMEM, "workspace allocation failed");
+    }
+    cap = count;
+    return SANS_OK;
+}
+
+int set_lds_limit(const void* fn, size_t shmem)
+{
+    if (shmem > 64 * 1024)
+        HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+    return SANS_OK;
 }
 
 int launch_fill(double* p, size_t n, hipStream_t s)
@@ -596,6 +784,9 @@ int sans_model_destroy(sans_model_t m)
     if (m->d_tab_norm) (void)hipFree(m->d_tab_norm);
     if (m->d_quad) (void)hipFree(m->d_quad);
     if (m->d_replicas) (void)hipFree(m->d_replicas);
+    if (m->d_partial) (void)hipFree(m->d_partial);
+    if (m->d_buckets) (void)hipFree(m->d_buckets);
+    if (m->d_bucket_count) (void)hipFree(m->d_bucket_count);
     delete m;
     return SANS_OK;
 }
@@ -629,7 +820,78 @@ int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uin
         }
     }
     if (n == 0) return SANS_OK;
-    const int tally = choose_tally(m);
+    const int tally = choose_tally(m, det_w2 != nullptr || det_count != nullptr);
+    TraceArgs a = m->args;
+    a.first = first;
+    a.n = n;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    a.exp_id = exp_id;
+    const unsigned fill_grid = (unsigned)((npix + 255) / 256);
+
+    if (tally == SANS_TALLY_LDS) {
+        const LdsLayout lay = layout(m, true);
+        const size_t shmem = lds_bytes(lay);
+        HistFn fn = pick_hist(m->p.kind, m->p.mode);
+        int rc = set_lds_limit((const void*)fn, shmem);
+        if (rc) return rc;
+        const uint64_t blocks_needed = (n + kHistBlock - 1) / kHistBlock;
+        const int per_cu = std::max(1, std::min(2, (int)(kLdsMax / shmem)));
+        const unsigned grid =
+            (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks_needed, (uint64_t)m->num_cu * per_cu));
+        if ((rc = ensure(m->d_partial, m->partial_cap, (size_t)grid * npix))) return rc;
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(kHistBlock), shmem, s, a, lay, m->d_partial);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_reduce_partials, dim3(fill_grid), dim3(256), 0, s, det, m->d_partial,
+                           (int)grid, (int)npix, 1);
+        HIP_TRY(hipGetLastError());
+        return SANS_OK;
+    }
+
+    if (tally == SANS_TALLY_BINNED) {
+        const int rows = (int)(kTileBytes / (sizeof(double) * m->p.nx));
+        const int ntiles = (m->p.ny + rows - 1) / rows;
+        const int tile_pixels = rows * m->p.nx;
+        const int slices = std::max(1, m->num_cu / ntiles);
+        const uint64_t chunk = std::min<uint64_t>(n, std::max<uint64_t>(1u << 20, (1ull << 27) / ntiles));
+        int rc;
+        if ((rc = ensure(m->d_partial, m->partial_cap, (size_t)ntiles * slices * tile_pixels))) return rc;
+        if ((rc = ensure(m->d_buckets, m->bucket_cap, (size_t)ntiles * chunk))) return rc;
+        if (!m->d_bucket_count) {
+            if (hipMalloc(&m->d_bucket_count, sizeof(unsigned) * kMaxTiles) != hipSuccess) {
+                m->d_bucket_count = nullptr;
+                return fail(SANS_E_NOMEM, "workspace allocation failed");
+            }
+        }
+        if ((rc = launch_fill(m->d_partial, (size_t)ntiles * slices * tile_pixels, s))) return rc;
+        const LdsLayout lay = layout(m, false);
+        const size_t shmem = lds_bytes(lay);
+        EmitFn efn = pick_emit(m->p.kind, m->p.mode);
+        if ((rc = set_lds_limit((const void*)efn, shmem))) return rc;
+        if ((rc = set_lds_limit((const void*)k_bin_accumulate, sizeof(double) * tile_pixels))) return rc;
+        for (uint64_t c0 = 0; c0 < n; c0 += chunk) {
+            TraceArgs ac = a;
+            ac.first = first + c0;
+            ac.n = std::min<uint64_t>(chunk, n - c0);
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kMaxTiles), 0, s, m->d_bucket_count, kMaxTiles);
+            HIP_TRY(hipGetLastError());
+            const uint64_t blocks_needed = (ac.n + kEmitBlock - 1) / kEmitBlock;
+            const unsigned egrid = (unsigned)std::max<uint64_t>(
+                1, std::min<uint64_t>(blocks_needed, (uint64_t)m->num_cu * 8));
+            hipLaunchKernelGGL(efn, dim3(egrid), dim3(kEmitBlock), shmem, s, ac, lay, m->d_buckets,
+                               m->d_bucket_count, (unsigned)chunk, tile_pixels, ntiles);
+            HIP_TRY(hipGetLastError());
+            hipLaunchKernelGGL(k_bin_accumulate, dim3((unsigned)(ntiles * slices)), dim3(kHistBlock),
+                               sizeof(double) * tile_pixels, s, m->d_buckets, m->d_bucket_count,
+                               (unsigned)chunk, tile_pixels, slices, m->d_partial);
+            HIP_TRY(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_reduce_binned, dim3(fill_grid), dim3(256), 0, s, det, m->d_partial,
+                           tile_pixels, slices, (int)npix, 1);
+        HIP_TRY(hipGetLastError());
+        return SANS_OK;
+    }
+
     if (tally == SANS_TALLY_XCD && m->replica_pix != npix) {
         if (m->d_replicas) HIP_TRY(hipFree(m->d_replicas));
         m->d_replicas = nullptr;
@@ -640,34 +902,22 @@ int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uin
         int rc = launch_fill(m->d_replicas, npix * kXcds, s);
         if (rc) return rc;
     }
-    TraceArgs a = m->args;
-    a.first = first;
-    a.n = n;
-    a.seed_lo = (uint32_t)seed;
-    a.seed_hi = (uint32_t)(seed >> 32);
-    a.exp_id = exp_id;
-    const LdsLayout lay = layout(m, tally == SANS_TALLY_LDS);
+    const LdsLayout lay = layout(m, false);
     const size_t shmem = lds_bytes(lay);
     TraceFn fn = pick_trace(m->p.kind, m->p.mode, tally);
     if (!fn) return fail(SANS_E_UNSUPPORTED, "no kernel for this model");
-    if (shmem > 64 * 1024)
-        HIP_TRY(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+    int rc = set_lds_limit((const void*)fn, shmem);
+    if (rc) return rc;
     // grid: enough waves to fill every CU; the kernel strides over the range
-    uint64_t blocks_needed = (n + kBlock - 1) / kBlock;
-    uint64_t max_blocks;
-    if (tally == SANS_TALLY_LDS) {
-        const int per_cu = std::max<int>(1, (int)(kLdsMax / std::max<size_t>(shmem, 1)));
-        max_blocks = (uint64_t)m->num_cu * std::min(per_cu, 8);
-    } else {
-        max_blocks = (uint64_t)m->num_cu * 8;
-    }
-    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(blocks_needed, max_blocks));
+    const uint64_t blocks_needed = (n + kBlock - 1) / kBlock;
+    const unsigned grid = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>(blocks_needed, (uint64_t)m->num_cu * 8));
     hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), shmem, s, a, lay, det, det_w2,
                        (unsigned long long*)det_count, m->d_replicas);
     HIP_TRY(hipGetLastError());
     if (tally == SANS_TALLY_XCD) {
-        hipLaunchKernelGGL(k_sum_replicas, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, det,
-                           m->d_replicas, (int)npix, 1);
+        hipLaunchKernelGGL(k_sum_replicas, dim3(fill_grid), dim3(256), 0, s, det, m->d_replicas,
+                           (int)npix, 1);
         HIP_TRY(hipGetLastError());
     }
     return SANS_OK;

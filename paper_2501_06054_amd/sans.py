@@ -27,7 +27,7 @@ SANS_ACCUMULATE = 1
 KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelepiped": 4}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
-TALLY = {"auto": 0, "global": 1, "lds": 2, "xcd": 3}
+TALLY = {"auto": 0, "global": 1, "lds": 2, "xcd": 3, "binned": 4}
 
 
 class SansError(RuntimeError):

@@ -141,7 +141,7 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
 
 
 @pytest.mark.parametrize("name", DET_CASES)
-@pytest.mark.parametrize("tally", ["auto", "global", "lds", "xcd"])
+@pytest.mark.parametrize("tally", ["auto", "global", "lds", "xcd", "binned"])
 def test_detector_parity(S, name, tally):
     p, _ = PER_NEUTRON[name]
     n, seed = 300_007, 5
