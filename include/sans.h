@@ -204,6 +204,32 @@ int sans_debug_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t n_bloc
  * SANS_E_UNSUPPORTED if the handle has no such table. */
 int sans_debug_table(sans_model_t m, int32_t which, double* out, int32_t n);
 
+/* Traces n_exp independent virtual experiments (the paper's high-throughput
+ * use: many models, parameters and neutron counts; Introduction and
+ * Conclusion) in one persistent launch.  Experiment e traces neutrons
+ * 0 .. n_neutrons[e]-1 with seed seeds[e] and experiment id e -- the same
+ * random streams and the same detector as sans_trace_ex(model(p[e]), 0,
+ * n_neutrons[e], seeds[e], e, ...) up to FP64 summation order.
+ *   p            host sans_params [n_exp]; Monte Carlo mode; all with the same
+ *                nx, ny and table_size; nx*ny*8 (+ table_size*8 if any
+ *                experiment is polydisperse) must fit in 160 KiB of LDS
+ *   n_neutrons   host uint64 [n_exp];  seeds: host uint64 [n_exp]
+ *   detectors_out device FP64 [n_exp][ny][nx], overwritten
+ *   tune_cache   NULL, or a path to a JSON file of tuned tile sizes: read when
+ *                it holds an entry for this batch shape, otherwise the tile
+ *                size is tuned by timing the batch on the stream (the output
+ *                is rewritten by the final run) and the entry is written.
+ * Work is split into tiles (experiment, neutron range) popped from a device
+ * queue; the sequence (clear, Schulz tables, queue reset, persistent kernel)
+ * is captured once per batch shape as a HIP graph and replayed afterwards.
+ * The library keeps the graph and its buffers until sans_batch_release(). */
+int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons,
+                     const uint64_t* seeds, double* detectors_out, const char* tune_cache,
+                     void* stream);
+
+/* Frees the batch path's cached buffers and graph. */
+int sans_batch_release(void);
+
 /* Evaluates, on the device, the weight factor F^2 that replaces the drawn
  * size and orientation in SANS_MODE_QUAD: the Schulz size average and, for
  * isotropic orientation, the orientation average of F^2 by Gauss-Legendre

@@ -57,6 +57,7 @@ constexpr int kMaxQuad = 256;
 // ---------------------------------------------------------------- arguments
 // Everything a trace kernel needs, passed by value as the kernel argument.
 struct TraceArgs {
+    int32_t kind;                 // model (the batched kernel switches on it per tile)
     // instrument, FP64
     double src_w, src_h, src_z;
     double slit_w, slit_h, slit_z;

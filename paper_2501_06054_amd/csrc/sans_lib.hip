@@ -18,7 +18,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <sstream>
 #include <new>
 #include <string>
 #include <vector>
@@ -313,6 +316,154 @@ __global__ __launch_bounds__(kBlock) void k_pq_avg(const TraceArgs a, LdsLayout 
     out[j] = quad_average<KIND>(a, lq, q[j], qv);
 }
 
+// ------------------------------------------------------------------ Schulz tables (FP64)
+// Quantiles y_k = F^-1((k + 1/2)/M) of the Schulz distribution (Gamma with
+// shape a = 1/p^2 and mean 1): the CDF is tabulated by integrating the density
+// over kSchulzPanels panels (16-point Gauss-Legendre each, prefix-summed in
+// LDS); each quantile is then refined inside its panel by safeguarded Newton
+// steps on C(y_j) + int_{y_j}^{y} pdf - u = 0.  One workgroup per table.
+constexpr int kSchulzPanels = 4096;
+constexpr int kSchulzBlock = 256;
+
+struct SchulzJob {
+    double a, lnorm, ymax;   // shape, log normaliser a ln a - lgamma(a), upper limit
+    unsigned long long out;  // offset of the table in the output array
+};
+
+struct GL16 {
+    double x[16], w[16];
+};
+
+__device__ __forceinline__ double schulz_pdf_d(double y, double a, double lnorm)
+{
+    return y > 0.0 ? exp(lnorm + (a - 1.0) * log(y) - a * y) : 0.0;
+}
+
+__device__ __forceinline__ double pdf_integral(double lo, double hi, double a, double lnorm,
+                                               const GL16& g)
+{
+    const double h = 0.5 * (hi - lo), c = 0.5 * (hi + lo);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s = __builtin_fma(g.w[i], schulz_pdf_d(__builtin_fma(h, g.x[i], c), a, lnorm), s);
+    return h * s;
+}
+
+__global__ __launch_bounds__(kSchulzBlock) void k_schulz_tables(const SchulzJob* jobs, int M,
+                                                                double* tables, const GL16 g)
+{
+    __shared__ double cdf[kSchulzPanels + 1];
+    __shared__ double part[kSchulzBlock];
+    const SchulzJob jb = jobs[blockIdx.x];
+    const double dy = jb.ymax / kSchulzPanels;
+    constexpr int per = kSchulzPanels / kSchulzBlock;
+    const int j0 = threadIdx.x * per;
+    double acc = 0.0;
+    for (int k = 0; k < per; ++k) {
+        acc += pdf_integral((j0 + k) * dy, (j0 + k + 1) * dy, jb.a, jb.lnorm, g);
+        cdf[j0 + k + 1] = acc;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int t = 0; t < kSchulzBlock; ++t) {
+            const double v = part[t];
+            part[t] = r;
+            r += v;
+        }
+        cdf[0] = 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < per; ++k) cdf[j0 + k + 1] += part[threadIdx.x];
+    __syncthreads();
+    const double total = cdf[kSchulzPanels];
+    for (int k = threadIdx.x; k < M; k += blockDim.x) {
+        const double u = (k + 0.5) / M * total;
+        int lo = 0, hi = kSchulzPanels;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cdf[mid] <= u) lo = mid; else hi = mid;
+        }
+        const int j = lo;
+        double ylo = j * dy, yhi = (j + 1) * dy;
+        double y = ylo + (u - cdf[j]) / fmax(cdf[j + 1] - cdf[j], 1e-300) * dy;
+        for (int it = 0; it < 60; ++it) {
+            const double gval = cdf[j] + pdf_integral(j * dy, y, jb.a, jb.lnorm, g) - u;
+            if (gval > 0.0) yhi = y; else ylo = y;
+            const double f = schulz_pdf_d(y, jb.a, jb.lnorm);
+            double yn = f > 0.0 ? y - gval / f : 0.5 * (ylo + yhi);
+            if (!(yn > ylo && yn < yhi)) yn = 0.5 * (ylo + yhi);
+            const bool done = fabs(yn - y) <= 1e-16 * y;
+            y = yn;
+            if (done) break;
+        }
+        tables[jb.out + k] = y;
+    }
+}
+
+// ------------------------------------------------------------------ batched experiments
+// Persistent kernel over a queue of tiles (experiment e, neutron range).
+// Each workgroup pops a tile, stages that experiment's Schulz table into LDS,
+// traces the tile into an LDS histogram of the experiment's detector and
+// adds the histogram to the detector.  The model is uniform per tile, so the
+// switch on it is a scalar branch; every workgroup leaves the loop when the
+// queue is exhausted.
+struct BatchTile {
+    unsigned e;
+    unsigned count;
+    unsigned long long first;
+};
+
+template <int KIND>
+__device__ __forceinline__ void batch_tile(const TraceArgs& a, unsigned long long first, unsigned count,
+                                           double* hist, const double* tab)
+{
+    for (unsigned j = threadIdx.x; j < count; j += blockDim.x) {
+        const Event ev = trace_neutron<KIND, 0>(a, first + j, tab, a.tab_norm, nullptr);
+        if (ev.pixel >= 0)
+            __hip_atomic_fetch_add(hist + ev.pixel, (double)ev.w, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+__global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restrict__ exps,
+                                                      const BatchTile* __restrict__ tiles, int ntiles,
+                                                      unsigned* counter, double* dets, int npix, int M)
+{
+    extern __shared__ double lds_d[];
+    double* hist = lds_d;
+    double* tab = lds_d + npix;
+    __shared__ int s_tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int ti = s_tile;
+        if (ti >= ntiles) break;
+        const BatchTile tl = tiles[ti];
+        const unsigned e = __builtin_amdgcn_readfirstlane(tl.e);
+        const TraceArgs& a = exps[e];
+        for (int i = threadIdx.x; i < npix; i += blockDim.x) hist[i] = 0.0;
+        if (a.tab_size)
+            for (int i = threadIdx.x; i < M; i += blockDim.x) tab[i] = a.tab_size[i];
+        __syncthreads();
+        switch (a.kind) {
+        case 0: batch_tile<0>(a, tl.first, tl.count, hist, tab); break;
+        case 1: batch_tile<1>(a, tl.first, tl.count, hist, tab); break;
+        case 2: batch_tile<2>(a, tl.first, tl.count, hist, tab); break;
+        case 3: batch_tile<3>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<4>(a, tl.first, tl.count, hist, tab); break;
+        }
+        __syncthreads();
+        double* det = dets + (size_t)e * npix;
+        for (int i = threadIdx.x; i < npix; i += blockDim.x) {
+            const double v = hist[i];
+            if (v != 0.0) __hip_atomic_fetch_add(det + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ dispatch tables
 using TraceFn = void (*)(const TraceArgs, LdsLayout, double*, double*, unsigned long long*, double*);
 using DebugFn = void (*)(const TraceArgs, LdsLayout, int32_t*, float*, float*);
@@ -485,16 +636,48 @@ int validate(const sans_params* p)
 }
 
 // Fills the model's constants and (re)builds tables when needed.
-int configure(sans_model_s* m, const sans_params* p)
+SchulzJob schulz_job(double p, unsigned long long out)
 {
-    int rc = validate(p);
-    if (rc) return rc;
-    const sans_params old = m->p;
-    const bool first = (m->d_tab_norm == nullptr && m->d_tab_size == nullptr && m->d_quad == nullptr
-                        && m->args.M == 0);
-    m->p = *p;
-    TraceArgs& a = m->args;
+    SchulzJob j;
+    j.a = 1.0 / (p * p);
+    j.lnorm = j.a * std::log(j.a) - std::lgamma(j.a);
+    j.ymax = 1.0 + 60.0 * p + 10.0 * p * p;
+    j.out = out;
+    return j;
+}
+
+const GL16& gl16_nodes()
+{
+    static GL16 g;
+    static std::once_flag once;
+    std::call_once(once, [] { host::gauss_legendre(16, g.x, g.w); });
+    return g;
+}
+
+// Builds njobs Schulz tables of M knots on the device (jobs on the host).
+int build_schulz_tables(const SchulzJob* jobs, int njobs, int M, double* d_tables, hipStream_t s)
+{
+    if (njobs <= 0) return SANS_OK;
+    SchulzJob* d_jobs = nullptr;
+    HIP_TRY(hipMalloc(&d_jobs, sizeof(SchulzJob) * njobs));
+    hipError_t e = hipMemcpyAsync(d_jobs, jobs, sizeof(SchulzJob) * njobs, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_schulz_tables, dim3(njobs), dim3(kSchulzBlock), 0, s, d_jobs, M, d_tables,
+                           gl16_nodes());
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_jobs);
+    if (e != hipSuccess) return fail(SANS_E_HIP, std::string("Schulz tables: ") + hipGetErrorString(e));
+    return SANS_OK;
+}
+
+// Constants of one experiment (everything but the tables and quadrature
+// nodes): geometry in FP64, physics constants, Percus-Yevick series.
+void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* wscale, double* omc)
+{
     std::memset(&a, 0, sizeof(a));
+    a.kind = p->kind;
     a.src_w = p->src_w;
     a.src_h = p->src_h;
     a.src_z = p->src_z;
@@ -507,8 +690,8 @@ int configure(sans_model_s* m, const sans_params* p)
     a.half_y = 0.5 * p->sample_h;
     a.half_z = 0.5 * p->sample_d;
     const double sh = std::sin(0.5 * p->cone_alpha);
-    m->omc = 2.0 * sh * sh;
-    a.omc = m->omc;
+    *omc = 2.0 * sh * sh;
+    a.omc = *omc;
     a.det_z = p->det_z;
     a.det_hw = 0.5 * p->det_w;
     a.det_hh = 0.5 * p->det_h;
@@ -516,10 +699,10 @@ int configure(sans_model_s* m, const sans_params* p)
     a.inv_py = p->ny / p->det_h;
     a.nx = p->nx;
     a.ny = p->ny;
-    m->mean_v = host::mean_volume(p->kind, p->size, p->shell, p->poly, p->poly_mask);
-    const double dOmega = 2.0 * 3.141592653589793 * m->omc;
-    m->wscale = 1e10 * dOmega * p->phi / m->mean_v;
-    a.wscale = m->wscale;
+    *mean_v = host::mean_volume(p->kind, p->size, p->shell, p->poly, p->poly_mask);
+    const double dOmega = 2.0 * 3.141592653589793 * *omc;
+    *wscale = 1e10 * dOmega * p->phi / *mean_v;
+    a.wscale = *wscale;
     for (int k = 0; k < 3; ++k) {
         a.size[k] = p->size[k];
         a.fsize[k] = (float)p->size[k];
@@ -562,6 +745,20 @@ int configure(sans_model_s* m, const sans_params* p)
         a.sq_24phi = (float)(24.0 * p->sq_phi);
     }
     a.M = p->table_size;
+}
+
+int configure(sans_model_s* m, const sans_params* p)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    const sans_params old = m->p;
+    const bool first = (m->d_tab_norm == nullptr && m->d_tab_size == nullptr && m->d_quad == nullptr
+                        && m->args.M == 0);
+    m->p = *p;
+    TraceArgs& a = m->args;
+    fill_constants(p, a, &m->mean_v, &m->wscale, &m->omc);
+    const bool aniso = p->kind >= 2;
+
 
     // tables
     const bool need_size = p->mode == SANS_MODE_MC && a.poly_on;
@@ -571,13 +768,16 @@ int configure(sans_model_s* m, const sans_params* p)
     const bool norm_same = !first && old.table_size == p->table_size && !m->h_tab_norm.empty();
     if (need_size) {
         if (!size_same) {
-            m->h_tab_size.assign(p->table_size, 0.0);
-            host::schulz_table(p->poly, p->table_size, m->h_tab_size.data());
             if (m->d_tab_size) HIP_TRY(hipFree(m->d_tab_size));
             m->d_tab_size = nullptr;
             HIP_TRY(hipMalloc(&m->d_tab_size, sizeof(double) * p->table_size));
-            HIP_TRY(hipMemcpy(m->d_tab_size, m->h_tab_size.data(), sizeof(double) * p->table_size,
-                              hipMemcpyHostToDevice));
+            const SchulzJob job = schulz_job(p->poly, 0);
+            int rc2 = build_schulz_tables(&job, 1, p->table_size, m->d_tab_size, nullptr);
+            if (rc2) return rc2;
+            HIP_TRY(hipStreamSynchronize(nullptr));
+            m->h_tab_size.assign(p->table_size, 0.0);
+            HIP_TRY(hipMemcpy(m->h_tab_size.data(), m->d_tab_size, sizeof(double) * p->table_size,
+                              hipMemcpyDeviceToHost));
         }
         a.tab_size = m->d_tab_size;
     }
@@ -990,6 +1190,284 @@ int sans_pq_avg(sans_model_t m, const float* q, const float* qvec, int64_t n, fl
     hipLaunchKernelGGL(pick_pq(m->p.kind), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
                        lds_bytes(lay), (hipStream_t)stream, m->args, lay, q, qvec, n, out);
     HIP_TRY(hipGetLastError());
+    return SANS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batch host side
+namespace {
+
+struct BatchCache {
+    std::mutex mu;
+    TraceArgs* d_exps = nullptr;
+    size_t exps_cap = 0;
+    BatchTile* d_tiles = nullptr;
+    size_t tiles_cap = 0;
+    SchulzJob* d_jobs = nullptr;
+    size_t jobs_cap = 0;
+    double* d_tables = nullptr;
+    size_t tables_cap = 0;
+    double* d_norm = nullptr;
+    int norm_M = 0;
+    unsigned* d_counter = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string graph_key;
+    std::map<std::string, long> tuned;  // key -> tile size (this process)
+
+    void release()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        graph_key.clear();
+        if (d_exps) (void)hipFree(d_exps);
+        if (d_tiles) (void)hipFree(d_tiles);
+        if (d_jobs) (void)hipFree(d_jobs);
+        if (d_tables) (void)hipFree(d_tables);
+        if (d_norm) (void)hipFree(d_norm);
+        if (d_counter) (void)hipFree(d_counter);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        d_exps = nullptr;
+        d_tiles = nullptr;
+        d_jobs = nullptr;
+        d_tables = nullptr;
+        d_norm = nullptr;
+        d_counter = nullptr;
+        cap_stream = nullptr;
+        exps_cap = tiles_cap = jobs_cap = tables_cap = 0;
+        norm_M = 0;
+    }
+};
+
+BatchCache& batch_cache()
+{
+    static BatchCache c;
+    return c;
+}
+
+constexpr long kDefaultTile = 1l << 18;
+const long kTileCandidates[] = {1l << 16, 1l << 17, 1l << 18, 1l << 19, 1l << 20};
+
+std::string tune_key(int n_exp, double total_n, int nx, int ny, int num_cu)
+{
+    std::ostringstream k;
+    k << "E" << n_exp << "_S" << (int)std::lround(std::log2(std::max(total_n, 1.0))) << "_D" << nx << "x"
+      << ny << "_CU" << num_cu;
+    return k.str();
+}
+
+// Tuning cache file: one JSON object, one entry per line:
+//   "key": {"tile": T, "ms": t},
+std::map<std::string, long> read_tune_cache(const char* path)
+{
+    std::map<std::string, long> out;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t q0 = line.find('"');
+        const size_t q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
+        const size_t t = line.find("\"tile\":");
+        if (q0 == std::string::npos || q1 == std::string::npos || t == std::string::npos) continue;
+        out[line.substr(q0 + 1, q1 - q0 - 1)] = std::atol(line.c_str() + t + 7);
+    }
+    return out;
+}
+
+void write_tune_cache(const char* path, const std::map<std::string, long>& tiles,
+                      const std::map<std::string, double>& ms)
+{
+    std::ofstream f(path, std::ios::trunc);
+    f << "{\n";
+    size_t i = 0;
+    for (const auto& kv : tiles) {
+        const auto it = ms.find(kv.first);
+        f << "\"" << kv.first << "\": {\"tile\": " << kv.second << ", \"ms\": "
+          << (it == ms.end() ? 0.0 : it->second) << "}" << (++i < tiles.size() ? "," : "") << "\n";
+    }
+    f << "}\n";
+}
+
+// Queues the batch on stream s with tile size T (graph captured once per shape).
+int run_batch(BatchCache& c, int n_exp, const std::vector<TraceArgs>& exps,
+              const std::vector<SchulzJob>& jobs, const uint64_t* n_neutrons, long T, int npix, int M,
+              double* dets, size_t lds, int num_cu, hipStream_t s)
+{
+    // tiles: whole tiles first, then the remainders, each group by decreasing size
+    std::vector<BatchTile> tiles;
+    std::vector<BatchTile> rest;
+    for (int e = 0; e < n_exp; ++e) {
+        uint64_t f = 0;
+        const uint64_t n = n_neutrons[e];
+        for (; f + (uint64_t)T <= n; f += T) tiles.push_back(BatchTile{(unsigned)e, (unsigned)T, f});
+        if (f < n) rest.push_back(BatchTile{(unsigned)e, (unsigned)(n - f), f});
+    }
+    std::stable_sort(rest.begin(), rest.end(),
+                     [](const BatchTile& x, const BatchTile& y) { return x.count > y.count; });
+    tiles.insert(tiles.end(), rest.begin(), rest.end());
+    const int ntiles = (int)tiles.size();
+    int rc;
+    if ((rc = ensure(c.d_tiles, c.tiles_cap, std::max<size_t>(1, tiles.size())))) return rc;
+    if (!tiles.empty())
+        HIP_TRY(hipMemcpyAsync(c.d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(),
+                               hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(c.d_exps, exps.data(), sizeof(TraceArgs) * n_exp, hipMemcpyHostToDevice, s));
+    if (!jobs.empty())
+        HIP_TRY(hipMemcpyAsync(c.d_jobs, jobs.data(), sizeof(SchulzJob) * jobs.size(),
+                               hipMemcpyHostToDevice, s));
+
+    std::ostringstream key;
+    key << n_exp << "/" << ntiles << "/" << jobs.size() << "/" << npix << "/" << M << "/" << dets << "/"
+        << c.d_exps << "/" << c.d_tiles << "/" << c.d_jobs << "/" << c.d_tables;
+    if (c.graph_key != key.str()) {
+        if (c.exec) (void)hipGraphExecDestroy(c.exec);
+        if (c.graph) (void)hipGraphDestroy(c.graph);
+        c.exec = nullptr;
+        c.graph = nullptr;
+        c.graph_key.clear();
+        if (!c.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
+        const size_t ndet = (size_t)n_exp * npix;
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)((ndet + 255) / 256)), dim3(256), 0, c.cap_stream, dets, ndet);
+        if (!jobs.empty())
+            hipLaunchKernelGGL(k_schulz_tables, dim3((unsigned)jobs.size()), dim3(kSchulzBlock), 0,
+                               c.cap_stream, c.d_jobs, M, c.d_tables, gl16_nodes());
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, c.cap_stream, c.d_counter, 1);
+        const unsigned grid = (unsigned)std::max(1, std::min(ntiles, num_cu));
+        hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kHistBlock), lds, c.cap_stream, c.d_exps, c.d_tiles,
+                           ntiles, c.d_counter, dets, npix, M);
+        hipError_t le = hipGetLastError();
+        hipError_t ee = hipStreamEndCapture(c.cap_stream, &c.graph);
+        if (le != hipSuccess) return fail(SANS_E_HIP, std::string("batch launch: ") + hipGetErrorString(le));
+        if (ee != hipSuccess) return fail(SANS_E_HIP, std::string("graph capture: ") + hipGetErrorString(ee));
+        HIP_TRY(hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0));
+        c.graph_key = key.str();
+    }
+    HIP_TRY(hipGraphLaunch(c.exec, s));
+    return SANS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons, const uint64_t* seeds,
+                     double* detectors_out, const char* tune_cache, void* stream)
+{
+    if (n_exp < 1 || !p || !n_neutrons || !seeds || !detectors_out)
+        return fail(SANS_E_INVALID_ARG, "batch: null argument or n_exp < 1");
+    const int nx = p[0].nx, ny = p[0].ny, M = p[0].table_size;
+    bool any_poly = false, any_norm = false;
+    double total_n = 0.0;
+    for (int e = 0; e < n_exp; ++e) {
+        int rc = validate(&p[e]);
+        if (rc) return rc;
+        if (p[e].mode != SANS_MODE_MC) return fail(SANS_E_UNSUPPORTED, "batch: Monte Carlo mode only");
+        if (p[e].nx != nx || p[e].ny != ny) return fail(SANS_E_INVALID_ARG, "batch: detectors must match");
+        if (p[e].table_size != M) return fail(SANS_E_INVALID_ARG, "batch: table_size must match");
+        if (n_neutrons[e] >= (1ull << 48)) return fail(SANS_E_INVALID_ARG, "batch: neutron count too large");
+        any_poly |= p[e].poly > 0.0;
+        any_norm |= p[e].kind >= 2 && p[e].orient_kind == SANS_ORIENT_GAUSSIAN;
+        total_n += (double)n_neutrons[e];
+    }
+    const int npix = nx * ny;
+    const size_t lds = sizeof(double) * ((size_t)npix + (any_poly ? M : 0));
+    if (lds > kLdsMax) return fail(SANS_E_UNSUPPORTED, "batch: detector and table exceed LDS");
+    int device = 0, num_cu = 256;
+    HIP_TRY(hipGetDevice(&device));
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess) num_cu = prop.multiProcessorCount;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    BatchCache& c = batch_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+
+    // per-experiment constants and table jobs
+    std::vector<TraceArgs> exps(n_exp);
+    std::vector<SchulzJob> jobs;
+    int rc;
+    if ((rc = ensure(c.d_exps, c.exps_cap, (size_t)n_exp))) return rc;
+    size_t ntab = 0;
+    for (int e = 0; e < n_exp; ++e) ntab += p[e].poly > 0.0;
+    if ((rc = ensure(c.d_tables, c.tables_cap, std::max<size_t>(1, ntab * M)))) return rc;
+    if ((rc = ensure(c.d_jobs, c.jobs_cap, std::max<size_t>(1, ntab)))) return rc;
+    if (!c.d_counter && hipMalloc(&c.d_counter, sizeof(unsigned)) != hipSuccess) {
+        c.d_counter = nullptr;
+        return fail(SANS_E_NOMEM, "batch: counter allocation failed");
+    }
+    if (any_norm && c.norm_M != M) {
+        std::vector<double> t(M);
+        for (int k = 0; k < M; ++k) t[k] = host::normal_quantile((k + 0.5) / M);
+        if (c.d_norm) HIP_TRY(hipFree(c.d_norm));
+        c.d_norm = nullptr;
+        c.norm_M = 0;
+        HIP_TRY(hipMalloc(&c.d_norm, sizeof(double) * M));
+        HIP_TRY(hipMemcpy(c.d_norm, t.data(), sizeof(double) * M, hipMemcpyHostToDevice));
+        c.norm_M = M;
+    }
+    for (int e = 0; e < n_exp; ++e) {
+        double mv, ws, omc;
+        fill_constants(&p[e], exps[e], &mv, &ws, &omc);
+        exps[e].seed_lo = (uint32_t)seeds[e];
+        exps[e].seed_hi = (uint32_t)(seeds[e] >> 32);
+        exps[e].exp_id = (uint32_t)e;
+        if (p[e].poly > 0.0) {
+            exps[e].tab_size = c.d_tables + jobs.size() * (size_t)M;
+            jobs.push_back(schulz_job(p[e].poly, (unsigned long long)(jobs.size() * (size_t)M)));
+        }
+        if (p[e].kind >= 2 && p[e].orient_kind == SANS_ORIENT_GAUSSIAN) exps[e].tab_norm = c.d_norm;
+    }
+    if ((rc = set_lds_limit((const void*)k_batch, lds))) return rc;
+
+    // tile size: tuning cache, else autotune (when a cache path is given), else default
+    const std::string key = tune_key(n_exp, total_n, nx, ny, num_cu);
+    long T = kDefaultTile;
+    std::map<std::string, long> file_tiles;
+    if (tune_cache) file_tiles = read_tune_cache(tune_cache);
+    if (tune_cache && file_tiles.count(key)) {
+        T = file_tiles[key];
+    } else if (c.tuned.count(key)) {
+        T = c.tuned[key];
+    } else if (tune_cache) {
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        double best = 1e300;
+        for (long cand : kTileCandidates) {
+            if ((rc = run_batch(c, n_exp, exps, jobs, n_neutrons, cand, npix, M, detectors_out, lds, num_cu, s)))
+                return rc;
+            HIP_TRY(hipEventRecord(e0, s));
+            if ((rc = run_batch(c, n_exp, exps, jobs, n_neutrons, cand, npix, M, detectors_out, lds, num_cu, s)))
+                return rc;
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                T = cand;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        file_tiles[key] = T;
+        std::map<std::string, double> ms;
+        ms[key] = best;
+        write_tune_cache(tune_cache, file_tiles, ms);
+    }
+    c.tuned[key] = T;
+    return run_batch(c, n_exp, exps, jobs, n_neutrons, T, npix, M, detectors_out, lds, num_cu, s);
+}
+
+int sans_batch_release(void)
+{
+    BatchCache& c = batch_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    c.release();
     return SANS_OK;
 }
 

@@ -69,13 +69,15 @@ def _load():
     L.sans_debug_table.argtypes = [vp, i32, P(C.c_double), i32]
     L.sans_pq_avg.argtypes = [vp, vp, vp, i64, vp, vp]
     L.sans_model_constants.argtypes = [vp, P(C.c_double)]
+    L.sans_trace_batch.argtypes = [C.c_int, P(sans_params), P(u64), P(u64), vp, C.c_char_p, vp]
+    L.sans_batch_release.argtypes = []
     L.sans_abi_params_size.restype = u32
     L.sans_status_string.argtypes = [C.c_int]
     L.sans_status_string.restype = C.c_char_p
     L.sans_last_error.restype = C.c_char_p
     for f in ("sans_model_create", "sans_model_destroy", "sans_trace", "sans_trace_ex",
               "sans_debug_trace", "sans_debug_philox", "sans_debug_table", "sans_pq_avg",
-              "sans_model_constants"):
+              "sans_model_constants", "sans_trace_batch", "sans_batch_release"):
         getattr(L, f).restype = C.c_int
     return L
 
@@ -193,6 +195,25 @@ def sans_model_constants(h):
     out = (C.c_double * 3)()
     _check(lib.sans_model_constants(h, out), "sans_model_constants")
     return tuple(out)
+
+
+def sans_trace_batch(params_list, n_neutrons, seeds, detectors_out, tune_cache=None,
+                     stream=None) -> None:
+    """params_list: list of dicts or sans_params; detectors_out: device float64
+    tensor [n_exp, ny, nx] (overwritten)."""
+    n = len(params_list)
+    arr = (sans_params * n)()
+    for e, p in enumerate(params_list):
+        arr[e] = p if isinstance(p, sans_params) else to_params(p)
+    nn = (C.c_uint64 * n)(*[int(x) for x in n_neutrons])
+    sd = (C.c_uint64 * n)(*[int(x) for x in seeds])
+    tc = tune_cache.encode() if tune_cache else None
+    _check(lib.sans_trace_batch(n, arr, nn, sd, _dev(detectors_out, torch.float64, "detectors_out"),
+                                tc, _stream(stream)), "sans_trace_batch")
+
+
+def sans_batch_release() -> None:
+    _check(lib.sans_batch_release(), "sans_batch_release")
 
 
 def sans_abi_params_size() -> int:
