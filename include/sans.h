@@ -243,6 +243,51 @@ int sans_pq_avg(sans_model_t m, const float* q, const float* qvec, int64_t n, fl
  * per-metre weight scale 1e10 * dOmega * phi / <V>, out[2] = 1 - cos alpha. */
 int sans_model_constants(sans_model_t m, double* out3);
 
+/* ---------------------------------------------------------------------------
+ * Learned surrogate of the exact average (the orientation- and size-averaged
+ * form factor that SANS_MODE_QUAD computes by quadrature).  Not in the paper:
+ * the paper averages by Monte Carlo draws only; this network replaces the
+ * quadrature inside the tracer.
+ *
+ * Network: 8 inputs -> 4 hidden layers of 256 SiLU units -> 1 output.
+ * Parameters (199,937), flat, in the order W0[8][256] b0[256] W1[256][256]
+ * b1[256] W2 b2 W3 b3 W4[256] b4[1], W_l stored [in][out].  "w_bf16" is that
+ * vector in BF16 (device), "w32" in FP32.  All matrix products are BF16 MFMA
+ * (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; operands are rounded to
+ * BF16 (round to nearest even) when they are loaded.
+ * ------------------------------------------------------------------------- */
+
+/* Number of parameters (199,937). */
+int64_t sans_mlp_param_count(void);
+
+/* Device workspace (bytes) that forward/backward need for n samples. */
+uint64_t sans_mlp_workspace_bytes(int64_t n);
+
+/* y[n] = net(x[n][8]) (device FP32).  The pre-activations and activations
+ * of every hidden layer are left in ws for a following sans_mlp_backward on
+ * the same x.  n <= 2^24. */
+int sans_mlp_forward(const void* w_bf16, const float* x, int64_t n, float* y, void* ws, void* stream);
+
+/* dw (device FP32 [199,937], overwritten) = d(sum_i dy_i y_i)/dw for the
+ * samples of the preceding sans_mlp_forward (same w, x, n, ws). */
+int sans_mlp_backward(const void* w_bf16, const float* x, const float* dy, int64_t n, float* dw,
+                      void* ws, void* stream);
+
+/* One Adam step (Kingma & Ba, 2015) on w32 with gradient dw and moments m, v
+ * (all device FP32 [n]); writes the BF16 copy w_bf16.  step >= 1. */
+int sans_adam_step(float* w32, void* w_bf16, const float* dw, float* m, float* v, int64_t n,
+                   float lr, float beta1, float beta2, float eps, int step, void* stream);
+
+/* Mean squared error of y against t (device FP32 [n]): dy = 2 (y - t)/n and,
+ * if loss is not NULL, loss[0] += sum (y - t)^2 / n. */
+int sans_mse_grad(const float* y, const float* t, int64_t n, float* dy, float* loss, void* stream);
+
+/* y[i] = BF16(x[i]) (round to nearest even), device arrays. */
+int sans_f32_to_bf16(const float* x, void* y, int64_t n, void* stream);
+
+/* Text of the last error of the surrogate entry points of this thread. */
+const char* sans_mlp_last_error(void);
+
 /* sizeof(sans_params) as compiled into the library (binding layout check). */
 uint32_t sans_abi_params_size(void);
 

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libsans.so")
-SOURCES = ["sans_lib.hip", "sans_host_math.cpp"]
+SOURCES = ["sans_lib.hip", "sans_mlp.hip", "sans_host_math.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

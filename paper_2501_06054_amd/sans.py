@@ -71,6 +71,19 @@ def _load():
     L.sans_model_constants.argtypes = [vp, P(C.c_double)]
     L.sans_trace_batch.argtypes = [C.c_int, P(sans_params), P(u64), P(u64), vp, C.c_char_p, vp]
     L.sans_batch_release.argtypes = []
+    L.sans_mlp_param_count.restype = i64
+    L.sans_mlp_workspace_bytes.argtypes = [i64]
+    L.sans_mlp_workspace_bytes.restype = u64
+    L.sans_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.sans_mlp_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.sans_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, C.c_float, C.c_float, C.c_float,
+                                 C.c_float, C.c_int, vp]
+    L.sans_mse_grad.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.sans_f32_to_bf16.argtypes = [vp, vp, i64, vp]
+    L.sans_mlp_last_error.restype = C.c_char_p
+    for f in ("sans_mlp_forward", "sans_mlp_backward", "sans_adam_step", "sans_mse_grad",
+              "sans_f32_to_bf16"):
+        getattr(L, f).restype = C.c_int
     L.sans_abi_params_size.restype = u32
     L.sans_status_string.argtypes = [C.c_int]
     L.sans_status_string.restype = C.c_char_p
@@ -214,6 +227,51 @@ def sans_trace_batch(params_list, n_neutrons, seeds, detectors_out, tune_cache=N
 
 def sans_batch_release() -> None:
     _check(lib.sans_batch_release(), "sans_batch_release")
+
+
+def _mcheck(rc: int, where: str):
+    if rc != SANS_OK:
+        raise SansError(rc, where, lib.sans_mlp_last_error().decode())
+
+
+def sans_mlp_param_count() -> int:
+    return int(lib.sans_mlp_param_count())
+
+
+def sans_mlp_workspace_bytes(n: int) -> int:
+    return int(lib.sans_mlp_workspace_bytes(n))
+
+
+def sans_mlp_forward(w_bf16, x, y, ws, stream=None) -> None:
+    _mcheck(lib.sans_mlp_forward(_dev(w_bf16, torch.bfloat16, "w_bf16"), _dev(x, torch.float32, "x"),
+                                 x.shape[0], _dev(y, torch.float32, "y"), _dev(ws, None, "ws"),
+                                 _stream(stream)), "sans_mlp_forward")
+
+
+def sans_mlp_backward(w_bf16, x, dy, dw, ws, stream=None) -> None:
+    _mcheck(lib.sans_mlp_backward(_dev(w_bf16, torch.bfloat16, "w_bf16"), _dev(x, torch.float32, "x"),
+                                  _dev(dy, torch.float32, "dy"), x.shape[0],
+                                  _dev(dw, torch.float32, "dw"), _dev(ws, None, "ws"),
+                                  _stream(stream)), "sans_mlp_backward")
+
+
+def sans_adam_step(w32, w_bf16, dw, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8,
+                   stream=None) -> None:
+    _mcheck(lib.sans_adam_step(_dev(w32, torch.float32, "w32"), _dev(w_bf16, torch.bfloat16, "w_bf16"),
+                               _dev(dw, torch.float32, "dw"), _dev(m, torch.float32, "m"),
+                               _dev(v, torch.float32, "v"), w32.numel(), lr, beta1, beta2, eps, step,
+                               _stream(stream)), "sans_adam_step")
+
+
+def sans_mse_grad(y, t, dy, loss=None, stream=None) -> None:
+    _mcheck(lib.sans_mse_grad(_dev(y, torch.float32, "y"), _dev(t, torch.float32, "t"), y.numel(),
+                              _dev(dy, torch.float32, "dy"), _dev(loss, torch.float32, "loss"),
+                              _stream(stream)), "sans_mse_grad")
+
+
+def sans_f32_to_bf16(x, y, stream=None) -> None:
+    _mcheck(lib.sans_f32_to_bf16(_dev(x, torch.float32, "x"), _dev(y, torch.bfloat16, "y"), x.numel(),
+                                 _stream(stream)), "sans_f32_to_bf16")
 
 
 def sans_abi_params_size() -> int:
