@@ -91,6 +91,11 @@ def lib():
         L.orc_trace.restype = i32
         L.orc_trace_debug.argtypes = [P(OrcParams), u64, u64, u64, u32, P(i32), P(d), P(d)]
         L.orc_trace_debug.restype = i32
+        L.orc_mlp_param_count.restype = C.c_int64
+        L.orc_bf16_round.argtypes = [d]
+        L.orc_bf16_round.restype = d
+        L.orc_mlp_forward.argtypes = [P(d), P(d), i32, P(d), i32, P(d), P(d)]
+        L.orc_mlp_backward.argtypes = [P(d), P(d), P(d), i32, P(d), i32]
         L.orc_trace_debug_ex.argtypes = [P(OrcParams), u64, u64, u64, u32, P(d)]
         L.orc_trace_debug_ex.restype = i32
         _LIB = L
@@ -263,3 +268,31 @@ def trace_debug_ex(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0) 
     if rc != 0:
         raise ValueError(f"oracle trace failed ({rc})")
     return out
+
+
+def bf16_round(v: float) -> float:
+    return lib().orc_bf16_round(v)
+
+
+def mlp_param_count() -> int:
+    return int(lib().orc_mlp_param_count())
+
+
+def mlp_forward(w: np.ndarray, x: np.ndarray, round_bf16: bool = False) -> np.ndarray:
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = x.shape[0]
+    y = np.zeros(n)
+    lib().orc_mlp_forward(_ptr(w, C.c_double), _ptr(x, C.c_double), n, _ptr(y, C.c_double),
+                          int(round_bf16), None, None)
+    return y
+
+
+def mlp_backward(w: np.ndarray, x: np.ndarray, dy: np.ndarray, round_bf16: bool = False) -> np.ndarray:
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    dy = np.ascontiguousarray(dy, dtype=np.float64)
+    dw = np.zeros(mlp_param_count())
+    lib().orc_mlp_backward(_ptr(w, C.c_double), _ptr(x, C.c_double), _ptr(dy, C.c_double), x.shape[0],
+                           _ptr(dw, C.c_double), int(round_bf16))
+    return dw

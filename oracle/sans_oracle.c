@@ -847,3 +847,137 @@ int orc_trace(const orc_params* p, uint64_t first, uint64_t n, uint64_t seed, ui
     ctx_free(&cx);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The surrogate network, plainly: 8 -> 256 -> 256 -> 256 -> 256 -> 1 with
+ * SiLU hidden units, parameters flat in the order W0[8][256] b0 W1[256][256]
+ * b1 W2 b2 W3 b3 W4[256] b4 (W stored [in][out]).  FP64 arithmetic; with
+ * round_bf16 set, every operand of a matrix product is first rounded to
+ * FP32 and then to BF16 (round to nearest even), the operand precision the
+ * device uses, so that the comparison isolates the accumulation.           */
+#define ORC_NIN 8
+#define ORC_NH 256
+#define ORC_NP 199937
+
+static long orc_offw(int l) { return l == 0 ? 0 : ORC_NIN * ORC_NH + ORC_NH + (long)(l - 1) * (ORC_NH * ORC_NH + ORC_NH); }
+static long orc_offb(int l) { return l == 0 ? ORC_NIN * ORC_NH : orc_offw(l) + (long)ORC_NH * ORC_NH; }
+static const long ORC_OFFW4 = ORC_NIN * ORC_NH + ORC_NH + 3L * (ORC_NH * ORC_NH + ORC_NH);
+
+double orc_bf16_round(double v)
+{
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    u &= 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static double op(double v, int r) { return r ? orc_bf16_round(v) : v; }
+static double orc_silu(double z) { return z / (1.0 + exp(-z)); }
+static double orc_silu_grad(double z)
+{
+    double s = 1.0 / (1.0 + exp(-z));
+    return s * (1.0 + z * (1.0 - s));
+}
+
+int64_t orc_mlp_param_count(void) { return ORC_NP; }
+
+/* Forward for n samples; z (optional, [4][n][256]) receives the
+ * pre-activations, h (optional, [4][n][256]) the activations. */
+void orc_mlp_forward(const double* w, const double* x, int32_t n, double* y, int32_t round_bf16,
+                     double* z, double* h)
+{
+    double* a = (double*)malloc(sizeof(double) * ORC_NH);
+    double* b = (double*)malloc(sizeof(double) * ORC_NH);
+    for (int i = 0; i < n; ++i) {
+        /* layer 0 */
+        for (int o = 0; o < ORC_NH; ++o) {
+            double s = 0.0;
+            for (int k = 0; k < ORC_NIN; ++k)
+                s += op(x[(long)i * ORC_NIN + k], round_bf16) * op(w[orc_offw(0) + (long)k * ORC_NH + o], round_bf16);
+            double zz = s + op(w[orc_offb(0) + o], round_bf16);
+            if (z) z[(long)i * ORC_NH + o] = zz;
+            a[o] = orc_silu(zz);
+            if (h) h[(long)i * ORC_NH + o] = a[o];
+        }
+        for (int l = 1; l < 4; ++l) {
+            for (int o = 0; o < ORC_NH; ++o) {
+                double s = 0.0;
+                for (int k = 0; k < ORC_NH; ++k)
+                    s += op(a[k], round_bf16) * op(w[orc_offw(l) + (long)k * ORC_NH + o], round_bf16);
+                double zz = s + op(w[orc_offb(l) + o], round_bf16);
+                if (z) z[((long)l * n + i) * ORC_NH + o] = zz;
+                b[o] = orc_silu(zz);
+                if (h) h[((long)l * n + i) * ORC_NH + o] = b[o];
+            }
+            memcpy(a, b, sizeof(double) * ORC_NH);
+        }
+        double s = 0.0;
+        for (int k = 0; k < ORC_NH; ++k) s += op(a[k], round_bf16) * op(w[ORC_OFFW4 + k], round_bf16);
+        y[i] = s + op(w[ORC_OFFW4 + ORC_NH], round_bf16);
+    }
+    free(a);
+    free(b);
+}
+
+/* dw = gradient of sum_i dy_i y_i over the parameters (chain rule written
+ * out layer by layer). */
+void orc_mlp_backward(const double* w, const double* x, const double* dy, int32_t n, double* dw,
+                      int32_t round_bf16)
+{
+    double* z = (double*)malloc(sizeof(double) * 4L * n * ORC_NH);
+    double* h = (double*)malloc(sizeof(double) * 4L * n * ORC_NH);
+    double* y = (double*)malloc(sizeof(double) * n);
+    double* g = (double*)malloc(sizeof(double) * (long)n * ORC_NH);
+    double* gn = (double*)malloc(sizeof(double) * (long)n * ORC_NH);
+    orc_mlp_forward(w, x, n, y, round_bf16, z, h);
+    memset(dw, 0, sizeof(double) * ORC_NP);
+    /* output layer */
+    for (int k = 0; k < ORC_NH; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += op(h[(3L * n + i) * ORC_NH + k], round_bf16) * op(dy[i], round_bf16);
+        dw[ORC_OFFW4 + k] = s;
+    }
+    {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += dy[i];
+        dw[ORC_OFFW4 + ORC_NH] = s;
+    }
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < ORC_NH; ++k)
+            g[(long)i * ORC_NH + k] = op(dy[i], round_bf16) * op(w[ORC_OFFW4 + k], round_bf16)
+                                    * orc_silu_grad(z[(3L * n + i) * ORC_NH + k]);
+    for (int l = 3; l >= 0; --l) {
+        int kin = l == 0 ? ORC_NIN : ORC_NH;
+        for (int k = 0; k < kin; ++k)
+            for (int o = 0; o < ORC_NH; ++o) {
+                double s = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    double hin = l == 0 ? x[(long)i * ORC_NIN + k] : h[((long)(l - 1) * n + i) * ORC_NH + k];
+                    s += op(hin, round_bf16) * op(g[(long)i * ORC_NH + o], round_bf16);
+                }
+                dw[orc_offw(l) + (long)k * ORC_NH + o] = s;
+            }
+        for (int o = 0; o < ORC_NH; ++o) {
+            double s = 0.0;
+            for (int i = 0; i < n; ++i) s += g[(long)i * ORC_NH + o];
+            dw[orc_offb(l) + o] = s;
+        }
+        if (l == 0) break;
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < ORC_NH; ++k) {
+                double s = 0.0;
+                for (int o = 0; o < ORC_NH; ++o)
+                    s += op(g[(long)i * ORC_NH + o], round_bf16) * op(w[orc_offw(l) + (long)k * ORC_NH + o], round_bf16);
+                gn[(long)i * ORC_NH + k] = s * orc_silu_grad(z[((long)(l - 1) * n + i) * ORC_NH + k]);
+            }
+        memcpy(g, gn, sizeof(double) * (long)n * ORC_NH);
+    }
+    free(z);
+    free(h);
+    free(y);
+    free(g);
+    free(gn);
+}

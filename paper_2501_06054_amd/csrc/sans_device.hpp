@@ -619,9 +619,12 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
         if constexpr (KIND >= kCylinder) project<KIND != kCylinder>(g, qvd, qa, qb, qc);
         const float f = amplitude_mc<KIND>(a, y, qd, qa, qb, qc);
         f2 = f * f;
-    } else {
+    } else if constexpr (MODE == 1) {
         const float qv[3] = {(float)qvd[0], (float)qvd[1], (float)qvd[2]};
         f2 = quad_average<KIND>(a, lq, q, qv);
+    } else {
+        // MODE 2 (surrogate): the caller multiplies by the network's <F^2>
+        f2 = 1.0f;
     }
     float w = (float)(len * a.wscale) * f2;
     if (a.sq_on) w *= py_sq(a, q);

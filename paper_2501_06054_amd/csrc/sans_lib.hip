@@ -29,6 +29,7 @@
 #include "../../include/sans.h"
 #include "sans_device.hpp"
 #include "sans_host_math.hpp"
+#include "sans_surrogate.hpp"
 
 using namespace sans;
 
@@ -464,6 +465,146 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
     }
 }
 
+// ------------------------------------------------------------------ surrogate mode
+// Inputs of the network for one neutron: ln(q s0), ln(s1/s0), ln(s2/s0), p.
+struct SurConst {
+    float ls0;            // ln(size[0])
+    float x1, x2, x3;     // the constant inputs of this model
+    float lo0, hi0;       // domain of ln(q s0)
+    float f2_0;           // <F^2>(0)
+};
+
+// Surrogate tracer.  Geometry and S(q) per lane; the network per wave (16
+// samples at a time, activations in registers); in-domain neutrons are
+// tallied with FP64 global atomics, the others queued for the exact pass.
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const mlp::bf16x8* __restrict__ pk,
+                                                      const __bf16* __restrict__ wts, const SurConst sc,
+                                                      double* det, unsigned long long* queue, unsigned* qcount)
+{
+    __shared__ float xs_all[kBlock / 64][64 * mlp::kIn];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float* xs = xs_all[wave];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < a.n; j0 += stride) {
+        const uint64_t j = j0 + threadIdx.x;
+        const bool valid = j < a.n;
+        Event ev{-1, 0.0f, 0.0f};
+        if (valid) ev = trace_neutron<KIND, 2>(a, a.first + j, nullptr, nullptr, nullptr);
+        const float x0 = __logf(ev.q) + sc.ls0;
+        const bool in_dom = valid && ev.pixel >= 0 && x0 >= sc.lo0 && x0 <= sc.hi0;
+        float* xr = xs + lane * mlp::kIn;
+        xr[0] = fminf(fmaxf(x0, sc.lo0), sc.hi0);
+        xr[1] = sc.x1;
+        xr[2] = sc.x2;
+        xr[3] = sc.x3;
+        xr[4] = xr[5] = xr[6] = xr[7] = 0.0f;
+        __syncthreads();
+        float y = 0.0f;
+#pragma unroll 1
+        for (int c = 0; c < 4; ++c) {
+            const float yc = sur::forward16(pk, wts, xs, c);
+            if ((lane >> 4) == c) y = yc;
+        }
+        __syncthreads();
+        if (in_dom) {
+            const double w = (double)(ev.w * sc.f2_0 * __expf(y));
+            __hip_atomic_fetch_add(det + ev.pixel, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (valid && ev.pixel >= 0) {
+            const unsigned slot = atomicAdd(qcount, 1u);
+            queue[slot] = a.first + j;
+        }
+    }
+}
+
+// Exact (quadrature) pass over the queued neutrons.
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_trace_queue(const TraceArgs a, LdsLayout lay,
+                                                        const unsigned long long* queue, const unsigned* qcount,
+                                                        double* det)
+{
+    extern __shared__ double lds_d[];
+    const LdsPtrs lp = stage_all(a, lay, lds_d);
+    __syncthreads();
+    const unsigned nq = *qcount;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += gridDim.x * blockDim.x) {
+        const Event ev = trace_neutron<KIND, 1>(a, queue[i], lp.tsize, lp.tnorm, lp.lq);
+        if (ev.pixel >= 0)
+            __hip_atomic_fetch_add(det + ev.pixel, (double)ev.w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Training targets: for inputs x = (ln(q s0), ln(s1/s0), ln(s2/s0), p, ...)
+// the exact ln(<F^2>(q) / <F^2>(0)) of an isotropically oriented particle
+// with sizes s0 (1, e^x1, e^x2), Schulz width p on all sizes.  Orientation
+// nodes in LDS as in quad_average; size nodes per sample from gx, gw.
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_pq_dataset(const TraceArgs a, const float* __restrict__ x,
+                                                       int64_t n, float* __restrict__ out,
+                                                       const float* __restrict__ nodes, int nq, int dims,
+                                                       const double* __restrict__ gl_x,
+                                                       const double* __restrict__ gl_w)
+{
+    __shared__ float lq[5 * kMaxQuad];
+    for (int i = threadIdx.x; i < 5 * nq; i += blockDim.x) lq[i] = nodes[i];
+    __syncthreads();
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const float* xi = x + idx * mlp::kIn;
+    const float q = __expf(xi[0]);
+    const float s1 = __expf(xi[1]), s2 = __expf(xi[2]);
+    const double pw = xi[3];
+    const float* mu = lq;
+    const float* wmu = lq + nq;
+    const float* cb = lq + 2 * nq;
+    const float* sb = lq + 3 * nq;
+    const float* wb = lq + 4 * nq;
+    const int ny = pw > 0.0 ? nq : 1;
+    double lo = 1.0, hi = 1.0, aa = 0.0, lnorm = 0.0;
+    if (pw > 0.0) {
+        lo = fmax(0.0, 1.0 - 6.0 * pw);
+        hi = 1.0 + 8.0 * pw;
+        aa = 1.0 / (pw * pw);
+        lnorm = aa * log(aa) - lgamma(aa);
+    }
+    double num = 0.0, den = 0.0, wsum = 0.0;
+    for (int j = 0; j < ny; ++j) {
+        double y = 1.0, wy = 1.0;
+        if (pw > 0.0) {
+            y = lo + 0.5 * (hi - lo) * (gl_x[j] + 1.0);
+            wy = y > 0.0 ? gl_w[j] * exp(lnorm + (aa - 1.0) * log(y) - aa * y) : 0.0;
+        }
+        const float s[3] = {(float)y, (float)(s1 * y), (float)(s2 * y)};
+        float avg = 0.0f;
+        if (dims == 1) {
+            for (int i = 0; i < nq; ++i) {
+                const float m = mu[i];
+                const float st = sqrtf(fmaxf(1.0f - m * m, 0.0f));
+                const float f = amplitude_f<KIND>(a, s, q, q * st, 0.0f, q * m);
+                avg = __builtin_fmaf(wmu[i], f * f, avg);
+            }
+        } else {
+            for (int i = 0; i < nq; ++i) {
+                const float m = mu[i];
+                const float qst = q * sqrtf(fmaxf(1.0f - m * m, 0.0f));
+                const float qc = q * m;
+                float inner = 0.0f;
+                for (int l = 0; l < nq; ++l) {
+                    const float f = amplitude_f<KIND>(a, s, q, qst * cb[l], qst * sb[l], qc);
+                    inner = __builtin_fmaf(wb[l], f * f, inner);
+                }
+                avg = __builtin_fmaf(wmu[i], inner, avg);
+            }
+        }
+        const float f0 = amplitude_f<KIND>(a, s, 0.0f, 0.0f, 0.0f, 0.0f);
+        num += wy * (double)avg;
+        den += wy * (double)f0 * (double)f0;
+        wsum += wy;
+    }
+    (void)wsum;
+    out[idx] = (float)log(num / den);
+}
+
 // ------------------------------------------------------------------ dispatch tables
 using TraceFn = void (*)(const TraceArgs, LdsLayout, double*, double*, unsigned long long*, double*);
 using DebugFn = void (*)(const TraceArgs, LdsLayout, int32_t*, float*, float*);
@@ -575,6 +716,15 @@ struct sans_model_s {
     uint2* d_buckets = nullptr;
     size_t bucket_cap = 0;      // events
     unsigned* d_bucket_count = nullptr;
+    // surrogate network (SANS_MODE_SURROGATE)
+    double sur_f2_0 = 0.0;      // <F^2>(q = 0) from the size nodes (normalisation of the target)
+    __bf16* d_sur_w = nullptr;  // flat BF16 parameters
+    mlp::bf16x8* d_sur_pack = nullptr;
+    float sur_lo[4] = {0, 0, 0, 0}, sur_hi[4] = {0, 0, 0, 0};
+    bool sur_attached = false;
+    unsigned long long* d_queue = nullptr;
+    size_t queue_cap = 0;
+    unsigned* d_qcount = nullptr;
     int device = 0;
     int num_cu = 256;
 };
@@ -589,8 +739,15 @@ int validate(const sans_params* p)
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
     if (p->kind < 0 || p->kind > 4) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
-    if (p->mode == SANS_MODE_SURROGATE)
-        return fail(SANS_E_UNSUPPORTED, "surrogate mode needs an attached network");
+    if (p->mode == SANS_MODE_SURROGATE) {
+        if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
+            return fail(SANS_E_UNSUPPORTED, "surrogate mode: ellipsoid or parallelepiped only");
+        if (p->orient_kind != SANS_ORIENT_ISOTROPIC)
+            return fail(SANS_E_UNSUPPORTED, "surrogate mode: isotropic orientation only");
+        if (p->kind == SANS_ELLIPSOID && p->size[0] != p->size[1])
+            return fail(SANS_E_UNSUPPORTED, "surrogate mode: ellipsoids of revolution (a = b) only");
+        if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
+    }
     if (p->orient_kind < 0 || p->orient_kind > 3) return fail(SANS_E_UNSUPPORTED, "unknown orientation kind");
     if (p->tally < 0 || p->tally > 4) return fail(SANS_E_UNSUPPORTED, "unknown tally strategy");
     const int nsize = p->kind <= 1 ? 1 : (p->kind == 2 ? 2 : 3);
@@ -797,7 +954,8 @@ int configure(sans_model_s* m, const sans_params* p)
 
     // quadrature nodes: mu in [0, 1], beta in [0, pi/2], size y in
     // [max(0, 1 - 6p), 1 + 8p] with Schulz weights normalised to sum 1
-    if (p->mode == SANS_MODE_QUAD) {
+    // (also the exact fallback and normalisation of the surrogate mode)
+    if (p->mode == SANS_MODE_QUAD || p->mode == SANS_MODE_SURROGATE) {
         const int n = p->quad_n;
         std::vector<double> gx(n), gw(n);
         host::gauss_legendre(n, gx.data(), gw.data());
@@ -843,6 +1001,18 @@ int configure(sans_model_s* m, const sans_params* p)
             m->h_quad[5 * n + j] = (float)ys[j];
             m->h_quad[5 * n + ny + j] = (float)wy[j];
         }
+        // <F^2> at q = 0 over the same size nodes: (drho V(y))^2 averaged
+        {
+            const double drho = p->sld[0] - p->sld[2];
+            double f2 = 0.0;
+            for (int j = 0; j < ny; ++j) {
+                double v = 1.0;
+                for (int k = 0; k < 3; ++k) v *= (p->poly_mask >> k & 1) ? p->size[k] * ys[j] : p->size[k];
+                if (p->kind == SANS_ELLIPSOID) v *= 4.0 / 3.0 * 3.141592653589793;
+                f2 += wy[j] * (drho * v) * (drho * v);
+            }
+            m->sur_f2_0 = f2;
+        }
         if (m->d_quad) HIP_TRY(hipFree(m->d_quad));
         m->d_quad = nullptr;
         HIP_TRY(hipMalloc(&m->d_quad, sizeof(float) * m->h_quad.size()));
@@ -865,7 +1035,7 @@ LdsLayout layout(const sans_model_s* m, bool hist)
     l.tab_norm = off;
     if (a.tab_norm) off += a.M;
     l.quad = off;
-    l.quad_floats = (m->p.mode == SANS_MODE_QUAD) ? 5 * a.quad_n + 2 * a.quad_ny : 0;
+    l.quad_floats = (m->p.mode != SANS_MODE_MC) ? 5 * a.quad_n + 2 * a.quad_ny : 0;
     off += (l.quad_floats + 1) / 2;
     l.total = off;
     return l;
@@ -987,6 +1157,10 @@ int sans_model_destroy(sans_model_t m)
     if (m->d_partial) (void)hipFree(m->d_partial);
     if (m->d_buckets) (void)hipFree(m->d_buckets);
     if (m->d_bucket_count) (void)hipFree(m->d_bucket_count);
+    if (m->d_sur_w) (void)hipFree(m->d_sur_w);
+    if (m->d_sur_pack) (void)hipFree(m->d_sur_pack);
+    if (m->d_queue) (void)hipFree(m->d_queue);
+    if (m->d_qcount) (void)hipFree(m->d_qcount);
     delete m;
     return SANS_OK;
 }

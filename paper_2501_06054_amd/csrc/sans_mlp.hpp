@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
 }
 
 // Column sums: out[n] = sum_m X[m][n]  (bias gradients).
-__global__ void k_colsum(const float* __restrict__ X, int M, int N, float* __restrict__ out)
+static __global__ void k_colsum(const float* __restrict__ X, int M, int N, float* __restrict__ out)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
@@ -149,7 +149,7 @@ __global__ void k_colsum(const float* __restrict__ X, int M, int N, float* __res
 }
 
 // Adam (Kingma & Ba, 2015) on the FP32 master weights; writes the BF16 copy.
-__global__ void k_adam(float* __restrict__ w, __bf16* __restrict__ wb, const float* __restrict__ g,
+static __global__ void k_adam(float* __restrict__ w, __bf16* __restrict__ wb, const float* __restrict__ g,
                        float* __restrict__ m, float* __restrict__ v, int64_t n, float lr, float b1,
                        float b2, float eps, float c1, float c2)
 {
@@ -166,7 +166,7 @@ __global__ void k_adam(float* __restrict__ w, __bf16* __restrict__ wb, const flo
 }
 
 // Mean-squared-error gradient: dy = 2 (y - t) / n, loss += sum (y - t)^2 / n.
-__global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, int64_t n,
+static __global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, int64_t n,
                       float* __restrict__ dy, float* __restrict__ loss)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -181,7 +181,7 @@ __global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, 
     if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, e);
 }
 
-__global__ void k_f32_to_bf16(const float* __restrict__ x, __bf16* __restrict__ y, int64_t n)
+static __global__ void k_f32_to_bf16(const float* __restrict__ x, __bf16* __restrict__ y, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] = (__bf16)x[i];

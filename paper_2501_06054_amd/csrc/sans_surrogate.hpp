@@ -1,0 +1,140 @@
+// sans_surrogate.hpp -- the surrogate network inside the tracer (gfx950).
+//
+// Every wave evaluates the network for its own 64 neutrons, 16 at a time,
+// with the activations held in registers from layer to layer:
+//   D[16 features][16 samples] += A[16 features][32 inputs] * B[32 inputs][16 samples]
+// (v_mfma_f32_16x16x32_bf16).  Lane (g = lane/16, r = lane%16) holds, for
+// output tile t, the features 16t + 4g + i (i = 0..3) of sample r.  The
+// reduction index of the next layer is ordered so that those values are
+// exactly the B operand the lane needs: K-step s, element j maps to input
+// 32s + (j < 4 ? 4g + j : 16 + 4g + j - 4) -- the outputs of tiles 2s and
+// 2s+1 of the lane itself.  The weights are pre-packed (k_pack_surrogate)
+// as A fragments in that order, 16 bytes per lane per (tile, K-step), read
+// from global memory (L2-resident, 390 KiB).
+#pragma once
+
+#include "sans_device.hpp"
+#include "sans_mlp.hpp"
+
+namespace sans {
+namespace sur {
+
+using mlp::bf16x8;
+using mlp::f32x4;
+using mlp::kHid;
+using mlp::kIn;
+
+constexpr int kTiles = kHid / 16;   // 16 output tiles per hidden layer
+constexpr int kSteps = kHid / 32;   // 8 K-steps per hidden layer
+// packed layout (bf16x8 units): layer 0: [tile][lane]; layers 1..3: [tile][step][lane]
+constexpr int64_t kPack0 = (int64_t)kTiles * 64;
+constexpr int64_t kPackL = (int64_t)kTiles * kSteps * 64;
+constexpr int64_t kPackTotal = kPack0 + 3 * kPackL;
+
+__host__ __device__ constexpr int perm_k(int g, int j) { return j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4); }
+
+// Packs the flat BF16 parameters into A fragments.  One thread per
+// (layer, tile, step, lane).
+static __global__ void k_pack_surrogate(const __bf16* __restrict__ w, bf16x8* __restrict__ out)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= kPackTotal) return;
+    const int lane = (int)(id % 64);
+    const int g = lane >> 4, r = lane & 15;
+    bf16x8 v;
+    if (id < kPack0) {
+        const int t = (int)(id / 64);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = perm_k(g, j);
+            v[j] = k < kIn ? w[mlp::offW(0) + (int64_t)k * kHid + 16 * t + r] : (__bf16)0.0f;
+        }
+    } else {
+        const int64_t rem = id - kPack0;
+        const int l = 1 + (int)(rem / kPackL);
+        const int64_t q = rem % kPackL;
+        const int t = (int)(q / (kSteps * 64));
+        const int s = (int)((q / 64) % kSteps);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 32 * s + perm_k(g, j);
+            v[j] = w[mlp::offW(l) + (int64_t)k * kHid + 16 * t + r];
+        }
+    }
+    out[id] = v;
+}
+
+// Bias + SiLU on an accumulator tile, converted to the next B operand half.
+__device__ __forceinline__ void act_to_bf16(const f32x4& acc, const __bf16* __restrict__ bias, int t, int g,
+                                            bf16x8& dst, int half)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float z = acc[i] + (float)bias[16 * t + 4 * g + i];
+        dst[4 * half + i] = (__bf16)mlp::silu(z);
+    }
+}
+
+// Network output for the 16 samples of column group c of this wave.  xs:
+// this wave's inputs in LDS, [64][8] floats.  Returns, in every lane with
+// g == c, the output for sample 16c + r (lane 16c + r).
+__device__ __forceinline__ float forward16(const bf16x8* __restrict__ pk, const __bf16* __restrict__ w,
+                                           const float* xs, int c)
+{
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, r = lane & 15;
+    // input operand: features perm_k(g, j) of sample 16c + r (zero beyond 8)
+    bf16x8 b0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int k = perm_k(g, j);
+        b0[j] = k < kIn ? (__bf16)xs[(16 * c + r) * kIn + k] : (__bf16)0.0f;
+    }
+    bf16x8 act[kSteps];
+    // layer 0
+#pragma unroll
+    for (int t = 0; t < kTiles; t += 2) {
+        f32x4 a0 = {0.0f, 0.0f, 0.0f, 0.0f}, a1 = {0.0f, 0.0f, 0.0f, 0.0f};
+        a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pk[(int64_t)t * 64 + lane], b0, a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pk[(int64_t)(t + 1) * 64 + lane], b0, a1, 0, 0, 0);
+        act_to_bf16(a0, w + mlp::offB(0), t, g, act[t / 2], 0);
+        act_to_bf16(a1, w + mlp::offB(0), t + 1, g, act[t / 2], 1);
+    }
+    // hidden layers 1..3
+    const bf16x8* p = pk + kPack0;
+#pragma unroll 1
+    for (int l = 1; l < 4; ++l) {
+        bf16x8 nxt[kSteps];
+#pragma unroll
+        for (int t = 0; t < kTiles; t += 2) {
+            f32x4 a0 = {0.0f, 0.0f, 0.0f, 0.0f}, a1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s = 0; s < kSteps; ++s) {
+                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(p[((int64_t)t * kSteps + s) * 64 + lane], act[s],
+                                                             a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    p[((int64_t)(t + 1) * kSteps + s) * 64 + lane], act[s], a1, 0, 0, 0);
+            }
+            act_to_bf16(a0, w + mlp::offB(l), t, g, nxt[t / 2], 0);
+            act_to_bf16(a1, w + mlp::offB(l), t + 1, g, nxt[t / 2], 1);
+        }
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) act[s] = nxt[s];
+        p += kPackL;
+    }
+    // output layer: sum over the lane's 64 features, then over the 4 groups
+    float y = 0.0f;
+#pragma unroll
+    for (int s = 0; s < kSteps; ++s)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 32 * s + perm_k(g, j);
+            y = __builtin_fmaf((float)act[s][j], (float)w[mlp::kOffW4 + k], y);
+        }
+    y += __shfl_xor(y, 16);
+    y += __shfl_xor(y, 32);
+    return y + (float)w[mlp::kOffB4];
+}
+
+}  // namespace sur
+}  // namespace sans
