@@ -288,6 +288,28 @@ int sans_f32_to_bf16(const float* x, void* y, int64_t n, void* stream);
 /* Text of the last error of the surrogate entry points of this thread. */
 const char* sans_mlp_last_error(void);
 
+/* Attaches a trained network to a model in SANS_MODE_SURROGATE (an
+ * ellipsoid of revolution, size[0] = size[1], or a parallelepiped, with
+ * isotropic orientation).  w_bf16: device BF16 parameters (copied).
+ * domain_lo/hi: host float[4], the training box of the physical inputs
+ * x = (ln(q size[0]), ln(size[1]/size[0]), ln(size[2]/size[0]), poly); the
+ * network sees u_k = (2 x_k - lo_k - hi_k)/(hi_k - lo_k) (0 where lo_k = hi_k).
+ * Tracing then weights a neutron by <F^2>(0) exp(net(u)) in place of the
+ * quadrature average <F^2>(q) of SANS_MODE_QUAD; neutrons whose q falls
+ * outside the box are queued and traced again with the exact quadrature (no
+ * divergent branch in the network kernel).  A model whose own shape lies
+ * outside the box is traced with the exact quadrature throughout. */
+int sans_model_attach_surrogate(sans_model_t m, const void* w_bf16, const float* domain_lo,
+                                const float* domain_hi);
+
+/* Training targets: out[i] = ln(<F^2>(q) / <F^2>(0)) of an isotropically
+ * oriented particle (kind SANS_ELLIPSOID: of revolution, 1D orientation
+ * average; SANS_PARALLELEPIPED: 2D) for physical inputs x[i][8] =
+ * (ln(q s0), ln(s1/s0), ln(s2/s0), poly, 0, 0, 0, 0) (device FP32), with
+ * quad_n Gauss-Legendre nodes per dimension and the Schulz size average when
+ * poly > 0 -- the same quadrature as SANS_MODE_QUAD.  Synchronous. */
+int sans_pq_dataset(int32_t kind, const float* x, int64_t n, float* out, int32_t quad_n, void* stream);
+
 /* sizeof(sans_params) as compiled into the library (binding layout check). */
 uint32_t sans_abi_params_size(void);
 

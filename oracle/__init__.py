@@ -20,7 +20,7 @@ SO = os.path.join(HERE, "liboracle.so")
 
 KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelepiped": 4}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
-MODE = {"mc": 0, "quad": 1}
+MODE = {"mc": 0, "quad": 1, "surrogate": 2}
 
 
 class OrcParams(C.Structure):
@@ -96,6 +96,7 @@ def lib():
         L.orc_bf16_round.restype = d
         L.orc_mlp_forward.argtypes = [P(d), P(d), i32, P(d), i32, P(d), P(d)]
         L.orc_mlp_backward.argtypes = [P(d), P(d), P(d), i32, P(d), i32]
+        L.orc_set_surrogate.argtypes = [P(d), P(d), P(d)]
         L.orc_trace_debug_ex.argtypes = [P(OrcParams), u64, u64, u64, u32, P(d)]
         L.orc_trace_debug_ex.restype = i32
         _LIB = L
@@ -296,3 +297,12 @@ def mlp_backward(w: np.ndarray, x: np.ndarray, dy: np.ndarray, round_bf16: bool 
     lib().orc_mlp_backward(_ptr(w, C.c_double), _ptr(x, C.c_double), _ptr(dy, C.c_double), x.shape[0],
                            _ptr(dw, C.c_double), int(round_bf16))
     return dw
+
+
+def set_surrogate(w: np.ndarray, lo, hi) -> None:
+    """Network (FP64 copy of the BF16 parameters) and input box of the
+    surrogate mode."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    lib().orc_set_surrogate(_ptr(w, C.c_double), _ptr(lo, C.c_double), _ptr(hi, C.c_double))

@@ -65,6 +65,10 @@ typedef struct {
     int32_t quad_n;        /* Gauss-Legendre order of the exact average      */
 } orc_params;
 
+/* Surrogate mode (mode 2): a network replaces the exact average; set with
+ * orc_set_surrogate.  Defined at the end of the file. */
+static double surrogate_f2(const orc_params* p, double q, int* in_domain);
+
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
  * easy as 1, 2, 3", SC'11): ten rounds of the 4x32 Philox S-box; the two key
@@ -606,7 +610,7 @@ static int ctx_init(orc_ctx* cx, const orc_params* p)
     cx->one_minus_cos = 2.0 * sh * sh;
     cx->prefactor = 2.0 * ORC_PI * cx->one_minus_cos * p->phi / orc_mean_volume(p);
     cx->third_block = (p->mode == 0) && (p->poly > 0.0 || p->orient_kind != 0);
-    if (p->mode == 1) {
+    if (p->mode >= 1) {
         if (p->quad_n < 1 || p->quad_n > ORC_MAX_QUAD) return -1;
         orc_gauss_legendre(p->quad_n, cx->gx, cx->gw);
     }
@@ -711,8 +715,12 @@ static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_
         }
         double f = orc_amplitude(p, q, qv, y, ang);
         f2 = f * f;
-    } else {
+    } else if (p->mode == 1) {
         f2 = pq_avg_nodes(p, q, qv, cx->gx, cx->gw);
+    } else {
+        int in_domain = 0;
+        f2 = surrogate_f2(p, q, &in_domain);
+        if (!in_domain) f2 = pq_avg_nodes(p, q, qv, cx->gx, cx->gw);
     }
     double sq = (p->sq_phi > 0.0) ? orc_py_sq(q, p->sq_radius, p->sq_phi) : 1.0;
     double w = len * 1e10 * cx->prefactor * f2 * sq;
@@ -980,4 +988,46 @@ void orc_mlp_backward(const double* w, const double* x, const double* dy, int32_
     free(y);
     free(g);
     free(gn);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Surrogate mode: the weight uses <F^2>(0) exp(net(u)) with the network's
+ * inputs u_k = (2 x_k - lo_k - hi_k)/(hi_k - lo_k) (0 where lo_k = hi_k) of
+ * x = (ln(q s0), ln(s1/s0), ln(s2/s0), p); outside the box the exact average
+ * is used.  The network runs with BF16 operand rounding (the device's
+ * operand precision).  <F^2>(0) is the exact average at q = 0.           */
+static double g_sur_w[ORC_NP];
+static double g_sur_lo[4], g_sur_hi[4];
+static int g_sur_set = 0;
+
+void orc_set_surrogate(const double* w, const double* lo, const double* hi)
+{
+    memcpy(g_sur_w, w, sizeof(double) * ORC_NP);
+    for (int k = 0; k < 4; ++k) {
+        g_sur_lo[k] = lo[k];
+        g_sur_hi[k] = hi[k];
+    }
+    g_sur_set = 1;
+}
+
+static double surrogate_f2(const orc_params* p, double q, int* in_domain)
+{
+    double x[4] = {log(q * p->size[0]), log(p->size[1] / p->size[0]), log(p->size[2] / p->size[0]), p->poly};
+    *in_domain = 0;
+    if (!g_sur_set) return 0.0;
+    double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k) {
+        if (!(x[k] >= g_sur_lo[k] - (k ? 1e-6 : 0.0) && x[k] <= g_sur_hi[k] + (k ? 1e-6 : 0.0))) return 0.0;
+        u[k] = g_sur_hi[k] > g_sur_lo[k] ? (2.0 * x[k] - g_sur_lo[k] - g_sur_hi[k]) / (g_sur_hi[k] - g_sur_lo[k]) : 0.0;
+    }
+    *in_domain = 1;
+    double y;
+    orc_mlp_forward(g_sur_w, u, 1, &y, 1, NULL, NULL);
+    double qv0[3] = {0.0, 0.0, 0.0};
+    double gx[ORC_MAX_QUAD], gw[ORC_MAX_QUAD];
+    orc_gauss_legendre(p->quad_n, gx, gw);
+    orc_params p0 = *p;
+    p0.mode = 1;
+    double f2_0 = pq_avg_nodes(&p0, 0.0, qv0, gx, gw);
+    return f2_0 * exp(y);
 }

@@ -434,7 +434,6 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
 {
     extern __shared__ double lds_d[];
     double* hist = lds_d;
-    double* tab = lds_d + npix;
     __shared__ int s_tile;
     for (;;) {
         if (threadIdx.x == 0) s_tile = (int)atomicAdd(counter, 1u);
@@ -445,8 +444,9 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         const unsigned e = __builtin_amdgcn_readfirstlane(tl.e);
         const TraceArgs& a = exps[e];
         for (int i = threadIdx.x; i < npix; i += blockDim.x) hist[i] = 0.0;
-        if (a.tab_size)
-            for (int i = threadIdx.x; i < M; i += blockDim.x) tab[i] = a.tab_size[i];
+        // the Schulz table stays in global memory (L2/L1): the histogram
+        // takes the workgroup's LDS
+        const double* tab = a.tab_size;
         __syncthreads();
         switch (a.kind) {
         case 0: batch_tile<0>(a, tl.first, tl.count, hist, tab); break;
@@ -471,6 +471,7 @@ struct SurConst {
     float ls0;            // ln(size[0])
     float x1, x2, x3;     // the constant inputs of this model
     float lo0, hi0;       // domain of ln(q s0)
+    float mid0, scale0;   // normalisation of ln(q s0): (x - mid0) * scale0
     float f2_0;           // <F^2>(0)
 };
 
@@ -485,6 +486,8 @@ __global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const m
     __shared__ float xs_all[kBlock / 64][64 * mlp::kIn];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float* xs = xs_all[wave];
+    const __amdgpu_buffer_rsrc_t rp = sur::make_rsrc(pk, (int)(16 * sur::kPackTotal));
+    const __amdgpu_buffer_rsrc_t rw = sur::make_rsrc(wts, (int)(2 * mlp::kParams));
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < a.n; j0 += stride) {
         const uint64_t j = j0 + threadIdx.x;
@@ -494,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const m
         const float x0 = __logf(ev.q) + sc.ls0;
         const bool in_dom = valid && ev.pixel >= 0 && x0 >= sc.lo0 && x0 <= sc.hi0;
         float* xr = xs + lane * mlp::kIn;
-        xr[0] = fminf(fmaxf(x0, sc.lo0), sc.hi0);
+        xr[0] = (fminf(fmaxf(x0, sc.lo0), sc.hi0) - sc.mid0) * sc.scale0;
         xr[1] = sc.x1;
         xr[2] = sc.x2;
         xr[3] = sc.x3;
@@ -503,7 +506,10 @@ __global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const m
         float y = 0.0f;
 #pragma unroll 1
         for (int c = 0; c < 4; ++c) {
-            const float yc = sur::forward16(pk, wts, xs, c);
+            // the weight loads must not be hoisted out of this loop (they
+            // would occupy hundreds of registers): opaque memory barrier
+            asm volatile("" ::: "memory");
+            const float yc = sur::forward16(rp, rw, xs, c);
             if ((lane >> 4) == c) y = yc;
         }
         __syncthreads();
@@ -1086,8 +1092,13 @@ int ensure(T*& ptr, size_t& cap, size_t count)
 
 int set_lds_limit(const void* fn, size_t shmem)
 {
-    if (shmem > 64 * 1024)
-        HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+    if (shmem > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();  // do not leave the error for the next call
+            return fail(SANS_E_HIP, std::string("LDS limit: ") + hipGetErrorString(e));
+        }
+    }
     return SANS_OK;
 }
 
@@ -1100,6 +1111,64 @@ int launch_fill(double* p, size_t n, hipStream_t s)
 }
 
 }  // namespace
+
+// Constant inputs of the surrogate for this model; false when they lie
+// outside the network's domain box.
+bool surrogate_inputs(const sans_model_s* m, SurConst& sc)
+{
+    const sans_params& p = m->p;
+    const double x[4] = {0.0, std::log(p.size[1] / p.size[0]), std::log(p.size[2] / p.size[0]), p.poly};
+    float u[4];
+    for (int k = 1; k < 4; ++k) {
+        const double lo = m->sur_lo[k], hi = m->sur_hi[k];
+        if (x[k] < lo - 1e-6 || x[k] > hi + 1e-6) return false;
+        u[k] = hi > lo ? (float)((2.0 * x[k] - lo - hi) / (hi - lo)) : 0.0f;
+    }
+    sc.ls0 = (float)std::log(p.size[0]);
+    sc.x1 = u[1];
+    sc.x2 = u[2];
+    sc.x3 = u[3];
+    sc.lo0 = m->sur_lo[0];
+    sc.hi0 = m->sur_hi[0];
+    sc.mid0 = 0.5f * (sc.lo0 + sc.hi0);
+    sc.scale0 = sc.hi0 > sc.lo0 ? 2.0f / (sc.hi0 - sc.lo0) : 0.0f;
+    sc.f2_0 = (float)m->sur_f2_0;
+    return true;
+}
+
+int run_surrogate(sans_model_s* m, const TraceArgs& a, const SurConst& sc, double* det, hipStream_t s)
+{
+    const uint64_t chunk = std::min<uint64_t>(a.n, 1ull << 22);
+    int rc;
+    if ((rc = ensure(m->d_queue, m->queue_cap, (size_t)chunk))) return rc;
+    if (!m->d_qcount && hipMalloc(&m->d_qcount, sizeof(unsigned)) != hipSuccess) {
+        m->d_qcount = nullptr;
+        return fail(SANS_E_NOMEM, "surrogate: counter allocation failed");
+    }
+    const LdsLayout lay = layout(m, false);
+    const size_t shmem = lds_bytes(lay);
+    for (uint64_t c0 = 0; c0 < a.n; c0 += chunk) {
+        TraceArgs ac = a;
+        ac.first = a.first + c0;
+        ac.n = std::min<uint64_t>(chunk, a.n - c0);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, m->d_qcount, 1);
+        const uint64_t blocks = (ac.n + kBlock - 1) / kBlock;
+        const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)m->num_cu * 8));
+        if (m->p.kind == SANS_PARALLELEPIPED) {
+            hipLaunchKernelGGL(k_trace_sur<kParallelepiped>, dim3(grid), dim3(kBlock), 0, s, ac, m->d_sur_pack,
+                               m->d_sur_w, sc, det, m->d_queue, m->d_qcount);
+            hipLaunchKernelGGL(k_trace_queue<kParallelepiped>, dim3((unsigned)m->num_cu * 2), dim3(kBlock), shmem, s,
+                               ac, lay, m->d_queue, m->d_qcount, det);
+        } else {
+            hipLaunchKernelGGL(k_trace_sur<kEllipsoid>, dim3(grid), dim3(kBlock), 0, s, ac, m->d_sur_pack,
+                               m->d_sur_w, sc, det, m->d_queue, m->d_qcount);
+            hipLaunchKernelGGL(k_trace_queue<kEllipsoid>, dim3((unsigned)m->num_cu * 2), dim3(kBlock), shmem, s,
+                               ac, lay, m->d_queue, m->d_qcount, det);
+        }
+        HIP_TRY(hipGetLastError());
+    }
+    return SANS_OK;
+}
 
 // ------------------------------------------------------------------ C ABI
 extern "C" {
@@ -1177,6 +1246,7 @@ int sans_model_constants(sans_model_t m, double* out3)
 int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
                   uint32_t flags, double* det, double* det_w2, uint64_t* det_count, void* stream)
 {
+    (void)hipGetLastError();  // a stale error of an earlier call is not ours
     if (!m || !det) return fail(SANS_E_INVALID_ARG, "model or detector is NULL");
     if (flags & ~SANS_ACCUMULATE) return fail(SANS_E_INVALID_ARG, "unknown flags");
     if (n > 0 && first + n < first) return fail(SANS_E_INVALID_ARG, "neutron range overflows");
@@ -1194,7 +1264,6 @@ int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uin
         }
     }
     if (n == 0) return SANS_OK;
-    const int tally = choose_tally(m, det_w2 != nullptr || det_count != nullptr);
     TraceArgs a = m->args;
     a.first = first;
     a.n = n;
@@ -1202,6 +1271,15 @@ int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uin
     a.seed_hi = (uint32_t)(seed >> 32);
     a.exp_id = exp_id;
     const unsigned fill_grid = (unsigned)((npix + 255) / 256);
+
+    if (m->p.mode == SANS_MODE_SURROGATE) {
+        if (det_w2 || det_count) return fail(SANS_E_UNSUPPORTED, "surrogate mode: no det_w2/det_count");
+        if (!m->sur_attached) return fail(SANS_E_UNSUPPORTED, "surrogate mode: no network attached");
+        SurConst sc;
+        if (surrogate_inputs(m, sc)) return run_surrogate(m, a, sc, det, s);
+        // the model's own shape lies outside the network's domain: exact path
+    }
+    const int tally = choose_tally(m, det_w2 != nullptr || det_count != nullptr);
 
     if (tally == SANS_TALLY_LDS) {
         const LdsLayout lay = layout(m, true);
@@ -1311,6 +1389,7 @@ int sans_trace(sans_model_t m, uint64_t n_neutrons, uint64_t seed, const sans_pa
 int sans_debug_trace(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
                      int32_t* pixel, float* w, float* q, void* stream)
 {
+    (void)hipGetLastError();  // a stale error of an earlier call is not ours
     if (!m) return fail(SANS_E_INVALID_ARG, "model is NULL");
     if (n == 0) return SANS_OK;
     if (n > (1ull << 31)) return fail(SANS_E_INVALID_ARG, "debug range limited to 2^31 neutrons");
@@ -1332,6 +1411,7 @@ int sans_debug_trace(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, 
 int sans_debug_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t n_blocks, uint32_t exp_id,
                       uint32_t* out, void* stream)
 {
+    (void)hipGetLastError();  // a stale error of an earlier call is not ours
     if (!out) return fail(SANS_E_INVALID_ARG, "out is NULL");
     if (n_blocks < 1 || n_blocks > 16) return fail(SANS_E_INVALID_ARG, "n_blocks must be in 1..16");
     if (n == 0) return SANS_OK;
@@ -1354,6 +1434,7 @@ int sans_debug_table(sans_model_t m, int32_t which, double* out, int32_t n)
 
 int sans_pq_avg(sans_model_t m, const float* q, const float* qvec, int64_t n, float* out, void* stream)
 {
+    (void)hipGetLastError();  // a stale error of an earlier call is not ours
     if (!m || !q || !out) return fail(SANS_E_INVALID_ARG, "NULL argument");
     if (m->p.mode != SANS_MODE_QUAD) return fail(SANS_E_UNSUPPORTED, "model is not in quadrature mode");
     if (n < 0) return fail(SANS_E_INVALID_ARG, "n < 0");
@@ -1364,6 +1445,80 @@ int sans_pq_avg(sans_model_t m, const float* q, const float* qvec, int64_t n, fl
     hipLaunchKernelGGL(pick_pq(m->p.kind), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
                        lds_bytes(lay), (hipStream_t)stream, m->args, lay, q, qvec, n, out);
     HIP_TRY(hipGetLastError());
+    return SANS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ surrogate C ABI
+extern "C" {
+
+int sans_model_attach_surrogate(sans_model_t m, const void* w_bf16, const float* domain_lo,
+                                const float* domain_hi)
+{
+    if (!m || !w_bf16 || !domain_lo || !domain_hi) return fail(SANS_E_INVALID_ARG, "NULL argument");
+    for (int k = 0; k < 4; ++k)
+        if (!(domain_hi[k] >= domain_lo[k])) return fail(SANS_E_INVALID_ARG, "domain_hi < domain_lo");
+    if (!m->d_sur_w) HIP_TRY(hipMalloc(&m->d_sur_w, sizeof(__bf16) * mlp::kParams));
+    if (!m->d_sur_pack) HIP_TRY(hipMalloc(&m->d_sur_pack, sizeof(mlp::bf16x8) * sur::kPackTotal));
+    HIP_TRY(hipMemcpy(m->d_sur_w, w_bf16, sizeof(__bf16) * mlp::kParams, hipMemcpyDeviceToDevice));
+    hipLaunchKernelGGL(sur::k_pack_surrogate, dim3((unsigned)((sur::kPackTotal + 255) / 256)), dim3(256), 0,
+                       nullptr, m->d_sur_w, m->d_sur_pack);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    for (int k = 0; k < 4; ++k) {
+        m->sur_lo[k] = domain_lo[k];
+        m->sur_hi[k] = domain_hi[k];
+    }
+    m->sur_attached = true;
+    return SANS_OK;
+}
+
+int sans_pq_dataset(int32_t kind, const float* x, int64_t n, float* out, int32_t quad_n, void* stream)
+{
+    if (!x || !out || n < 0) return fail(SANS_E_INVALID_ARG, "dataset: bad argument");
+    if (kind != SANS_ELLIPSOID && kind != SANS_PARALLELEPIPED)
+        return fail(SANS_E_UNSUPPORTED, "dataset: ellipsoid (of revolution) or parallelepiped");
+    if (quad_n < 1 || quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
+    if (n == 0) return SANS_OK;
+    const int nq = quad_n;
+    std::vector<double> gx(nq), gw(nq);
+    host::gauss_legendre(nq, gx.data(), gw.data());
+    std::vector<float> nodes(5 * nq);
+    for (int i = 0; i < nq; ++i) {
+        const double beta = 0.25 * 3.141592653589793 * (gx[i] + 1.0);
+        nodes[i] = (float)(0.5 * (gx[i] + 1.0));
+        nodes[nq + i] = (float)(0.5 * gw[i]);
+        nodes[2 * nq + i] = (float)std::cos(beta);
+        nodes[3 * nq + i] = (float)std::sin(beta);
+        nodes[4 * nq + i] = (float)(0.5 * gw[i]);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    float* d_nodes = nullptr;
+    double* d_gl = nullptr;
+    HIP_TRY(hipMalloc(&d_nodes, sizeof(float) * nodes.size()));
+    hipError_t e = hipMalloc(&d_gl, sizeof(double) * 2 * nq);
+    if (e == hipSuccess) e = hipMemcpy(d_nodes, nodes.data(), sizeof(float) * nodes.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_gl, gx.data(), sizeof(double) * nq, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_gl + nq, gw.data(), sizeof(double) * nq, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        TraceArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.contrast = 1.0f;
+        a.poly_mask = 7;
+        const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
+        if (kind == SANS_PARALLELEPIPED)
+            hipLaunchKernelGGL(k_pq_dataset<kParallelepiped>, dim3(grid), dim3(kBlock), 0, s, a, x, n, out, d_nodes,
+                               nq, 2, d_gl, d_gl + nq);
+        else
+            hipLaunchKernelGGL(k_pq_dataset<kEllipsoid>, dim3(grid), dim3(kBlock), 0, s, a, x, n, out, d_nodes, nq,
+                               1, d_gl, d_gl + nq);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_nodes);
+    if (d_gl) (void)hipFree(d_gl);
+    if (e != hipSuccess) return fail(SANS_E_HIP, std::string("dataset: ") + hipGetErrorString(e));
     return SANS_OK;
 }
 
@@ -1531,6 +1686,7 @@ extern "C" {
 int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons, const uint64_t* seeds,
                      double* detectors_out, const char* tune_cache, void* stream)
 {
+    (void)hipGetLastError();  // a stale error of an earlier call is not ours
     if (n_exp < 1 || !p || !n_neutrons || !seeds || !detectors_out)
         return fail(SANS_E_INVALID_ARG, "batch: null argument or n_exp < 1");
     const int nx = p[0].nx, ny = p[0].ny, M = p[0].table_size;
@@ -1548,8 +1704,8 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
         total_n += (double)n_neutrons[e];
     }
     const int npix = nx * ny;
-    const size_t lds = sizeof(double) * ((size_t)npix + (any_poly ? M : 0));
-    if (lds > kLdsMax) return fail(SANS_E_UNSUPPORTED, "batch: detector and table exceed LDS");
+    const size_t lds = sizeof(double) * (size_t)npix;
+    if (lds + 64 > kLdsMax) return fail(SANS_E_UNSUPPORTED, "batch: detector exceeds LDS");
     int device = 0, num_cu = 256;
     HIP_TRY(hipGetDevice(&device));
     {

@@ -64,25 +64,53 @@ static __global__ void k_pack_surrogate(const __bf16* __restrict__ w, bf16x8* __
     out[id] = v;
 }
 
-// Bias + SiLU on an accumulator tile, converted to the next B operand half.
-__device__ __forceinline__ void act_to_bf16(const f32x4& acc, const __bf16* __restrict__ bias, int t, int g,
-                                            bf16x8& dst, int half)
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+
+// Buffer resources (base, size) for the packed fragments and the flat
+// parameters: loads then take one lane offset in a VGPR and the tile/step
+// offset in an SGPR, instead of a 64-bit address per fragment; reads past
+// the end return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int bytes)
 {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, 0x00020000);
+}
+
+__device__ __forceinline__ bf16x8 load_frag(__amdgpu_buffer_rsrc_t r, int lane_off, int soff)
+{
+    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, soff, 0));
+}
+
+// four consecutive BF16 parameters starting at element e0 + 4g, as floats
+__device__ __forceinline__ void load4(__amdgpu_buffer_rsrc_t r, int g, int64_t e0, float v[4])
+{
+    const i32x2 raw = __builtin_amdgcn_raw_buffer_load_b64(r, 8 * g, (int)(2 * e0), 0);
+    const uint32_t lo = (uint32_t)raw[0], hi = (uint32_t)raw[1];
+    v[0] = __uint_as_float(lo << 16);
+    v[1] = __uint_as_float(lo & 0xFFFF0000u);
+    v[2] = __uint_as_float(hi << 16);
+    v[3] = __uint_as_float(hi & 0xFFFF0000u);
+}
+
+// Bias + SiLU on an accumulator tile, converted to the next B operand half.
+__device__ __forceinline__ void act_to_bf16(const f32x4& acc, __amdgpu_buffer_rsrc_t rw, int64_t boff, int t,
+                                            int g, bf16x8& dst, int half)
+{
+    float b[4];
+    load4(rw, g, boff + 16 * t, b);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const float z = acc[i] + (float)bias[16 * t + 4 * g + i];
-        dst[4 * half + i] = (__bf16)mlp::silu(z);
-    }
+    for (int i = 0; i < 4; ++i) dst[4 * half + i] = (__bf16)mlp::silu(acc[i] + b[i]);
 }
 
 // Network output for the 16 samples of column group c of this wave.  xs:
 // this wave's inputs in LDS, [64][8] floats.  Returns, in every lane with
 // g == c, the output for sample 16c + r (lane 16c + r).
-__device__ __forceinline__ float forward16(const bf16x8* __restrict__ pk, const __bf16* __restrict__ w,
-                                           const float* xs, int c)
+__device__ __forceinline__ float forward16(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rw, const float* xs,
+                                           int c)
 {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
+    const int loff = 16 * lane;
     // input operand: features perm_k(g, j) of sample 16c + r (zero beyond 8)
     bf16x8 b0;
 #pragma unroll
@@ -95,45 +123,51 @@ __device__ __forceinline__ float forward16(const bf16x8* __restrict__ pk, const 
 #pragma unroll
     for (int t = 0; t < kTiles; t += 2) {
         f32x4 a0 = {0.0f, 0.0f, 0.0f, 0.0f}, a1 = {0.0f, 0.0f, 0.0f, 0.0f};
-        a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pk[(int64_t)t * 64 + lane], b0, a0, 0, 0, 0);
-        a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pk[(int64_t)(t + 1) * 64 + lane], b0, a1, 0, 0, 0);
-        act_to_bf16(a0, w + mlp::offB(0), t, g, act[t / 2], 0);
-        act_to_bf16(a1, w + mlp::offB(0), t + 1, g, act[t / 2], 1);
+        a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load_frag(rp, loff, 1024 * t), b0, a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load_frag(rp, loff, 1024 * (t + 1)), b0, a1, 0, 0, 0);
+        act_to_bf16(a0, rw, mlp::offB(0), t, g, act[t / 2], 0);
+        act_to_bf16(a1, rw, mlp::offB(0), t + 1, g, act[t / 2], 1);
     }
     // hidden layers 1..3
-    const bf16x8* p = pk + kPack0;
 #pragma unroll 1
     for (int l = 1; l < 4; ++l) {
+        asm volatile("" ::: "memory");
+        const int base = (int)(16 * (kPack0 + (int64_t)(l - 1) * kPackL));
         bf16x8 nxt[kSteps];
 #pragma unroll
         for (int t = 0; t < kTiles; t += 2) {
             f32x4 a0 = {0.0f, 0.0f, 0.0f, 0.0f}, a1 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int s = 0; s < kSteps; ++s) {
-                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(p[((int64_t)t * kSteps + s) * 64 + lane], act[s],
-                                                             a0, 0, 0, 0);
+                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load_frag(rp, loff, base + 1024 * (t * kSteps + s)),
+                                                             act[s], a0, 0, 0, 0);
                 a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    p[((int64_t)(t + 1) * kSteps + s) * 64 + lane], act[s], a1, 0, 0, 0);
+                    load_frag(rp, loff, base + 1024 * ((t + 1) * kSteps + s)), act[s], a1, 0, 0, 0);
             }
-            act_to_bf16(a0, w + mlp::offB(l), t, g, nxt[t / 2], 0);
-            act_to_bf16(a1, w + mlp::offB(l), t + 1, g, nxt[t / 2], 1);
+            act_to_bf16(a0, rw, mlp::offB(l), t, g, nxt[t / 2], 0);
+            act_to_bf16(a1, rw, mlp::offB(l), t + 1, g, nxt[t / 2], 1);
         }
 #pragma unroll
         for (int s = 0; s < kSteps; ++s) act[s] = nxt[s];
-        p += kPackL;
     }
     // output layer: sum over the lane's 64 features, then over the 4 groups
     float y = 0.0f;
 #pragma unroll
-    for (int s = 0; s < kSteps; ++s)
+    for (int s = 0; s < kSteps; ++s) {
+        float wa[4], wb[4];
+        load4(rw, g, mlp::kOffW4 + 32 * s, wa);
+        load4(rw, g, mlp::kOffW4 + 32 * s + 16, wb);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = 32 * s + perm_k(g, j);
-            y = __builtin_fmaf((float)act[s][j], (float)w[mlp::kOffW4 + k], y);
+        for (int j = 0; j < 4; ++j) {
+            y = __builtin_fmaf((float)act[s][j], wa[j], y);
+            y = __builtin_fmaf((float)act[s][4 + j], wb[j], y);
         }
+    }
     y += __shfl_xor(y, 16);
     y += __shfl_xor(y, 32);
-    return y + (float)w[mlp::kOffB4];
+    float b4[4];
+    load4(rw, 0, mlp::kOffB4, b4);
+    return y + b4[0];
 }
 
 }  // namespace sur

@@ -71,6 +71,10 @@ def _load():
     L.sans_model_constants.argtypes = [vp, P(C.c_double)]
     L.sans_trace_batch.argtypes = [C.c_int, P(sans_params), P(u64), P(u64), vp, C.c_char_p, vp]
     L.sans_batch_release.argtypes = []
+    L.sans_model_attach_surrogate.argtypes = [vp, vp, P(C.c_float), P(C.c_float)]
+    L.sans_model_attach_surrogate.restype = C.c_int
+    L.sans_pq_dataset.argtypes = [i32, vp, i64, vp, i32, vp]
+    L.sans_pq_dataset.restype = C.c_int
     L.sans_mlp_param_count.restype = i64
     L.sans_mlp_workspace_bytes.argtypes = [i64]
     L.sans_mlp_workspace_bytes.restype = u64

@@ -1,0 +1,140 @@
+"""Training and use of the learned surrogate of the exact orientation/size
+average (SANS_MODE_SURROGATE).
+
+Everything numerical runs in libsans kernels: targets (sans_pq_dataset, the
+same Gauss-Legendre quadrature as SANS_MODE_QUAD), forward and backward
+passes (BF16 MFMA GEMMs), the MSE gradient and Adam.  PyTorch holds the
+device buffers and shuffles the dataset once per epoch.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import sans
+from . import workloads as W
+
+KIND = {"parallelepiped": sans.KIND["parallelepiped"], "spheroid": sans.KIND["ellipsoid"]}
+
+
+def normalise(x: np.ndarray | torch.Tensor, lo, hi):
+    """u_k = (2 x_k - lo_k - hi_k)/(hi_k - lo_k) for the first 4 inputs (0
+    where lo_k = hi_k); the other inputs stay 0."""
+    u = x.clone() if isinstance(x, torch.Tensor) else x.copy()
+    for k in range(4):
+        if hi[k] > lo[k]:
+            u[:, k] = (2 * x[:, k] - lo[k] - hi[k]) / (hi[k] - lo[k])
+        else:
+            u[:, k] = 0.0
+    return u
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-normal weights, zero biases, in the flat parameter order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    fan = [8, 256, 256, 256]
+    for l in range(4):
+        parts.append(rng.normal(0.0, math.sqrt(2.0 / fan[l]), size=fan[l] * 256))
+        parts.append(np.zeros(256))
+    parts.append(rng.normal(0.0, math.sqrt(1.0 / 256), size=256))
+    parts.append(np.zeros(1))
+    w = np.concatenate(parts).astype(np.float32)
+    assert w.size == sans.sans_mlp_param_count()
+    return w
+
+
+def make_dataset(model: str, n: int, seed: int, quad_n: int = 76):
+    """(u, t) on the device: normalised inputs and exact targets."""
+    x = torch.from_numpy(W.surrogate_inputs(model, n, seed)).cuda()
+    t = torch.empty(n, dtype=torch.float32, device="cuda")
+    chunk = 1 << 20
+    for i in range(0, n, chunk):
+        xi = x[i:i + chunk].contiguous()
+        ti = torch.empty(xi.shape[0], dtype=torch.float32, device="cuda")
+        rc = sans.lib.sans_pq_dataset(KIND[model], sans.C.c_void_p(xi.data_ptr()), xi.shape[0],
+                                      sans.C.c_void_p(ti.data_ptr()), quad_n,
+                                      sans.C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        if rc != 0:
+            raise sans.SansError(rc, "sans_pq_dataset", sans.lib.sans_last_error().decode())
+        t[i:i + chunk] = ti
+    lo, hi = W.SURROGATE_BOX[model]
+    return normalise(x, lo, hi).contiguous(), t
+
+
+class Surrogate:
+    """A network with FP32 master weights, its BF16 copy and Adam state."""
+
+    def __init__(self, model: str, seed: int = 0):
+        self.model = model
+        self.lo, self.hi = W.SURROGATE_BOX[model]
+        w = torch.from_numpy(init_params(seed)).cuda()
+        self.w32 = w
+        self.wb = torch.empty(w.numel(), dtype=torch.bfloat16, device="cuda")
+        sans.sans_f32_to_bf16(self.w32, self.wb)
+        self.m = torch.zeros_like(w)
+        self.v = torch.zeros_like(w)
+        self.dw = torch.zeros_like(w)
+        self.step_count = 0
+        self._ws = None
+        self._ws_n = 0
+
+    def _workspace(self, n: int):
+        if self._ws is None or self._ws_n < n:
+            nbytes = sans.sans_mlp_workspace_bytes(n)
+            self._ws = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+            self._ws_n = n
+        return self._ws
+
+    def predict(self, u: torch.Tensor, batch: int = 1 << 16) -> torch.Tensor:
+        out = torch.empty(u.shape[0], dtype=torch.float32, device="cuda")
+        for i in range(0, u.shape[0], batch):
+            ui = u[i:i + batch].contiguous()
+            yi = torch.empty(ui.shape[0], dtype=torch.float32, device="cuda")
+            sans.sans_mlp_forward(self.wb, ui, yi, self._workspace(ui.shape[0]))
+            out[i:i + batch] = yi
+        return out
+
+    def train(self, u: torch.Tensor, t: torch.Tensor, steps: int, batch: int = 4096,
+              lr: float = 2e-3, lr_min: float = 2e-5, seed: int = 0, log_every: int = 0):
+        """Adam with cosine learning-rate decay over `steps` minibatches; the
+        dataset is reshuffled every epoch.  Returns the loss history."""
+        n = u.shape[0]
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed)
+        y = torch.empty(batch, dtype=torch.float32, device="cuda")
+        dy = torch.empty(batch, dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        ws = self._workspace(batch)
+        hist = []
+        pos = n
+        us = ts = None
+        t0 = time.perf_counter()
+        for k in range(steps):
+            if pos + batch > n:
+                perm = torch.randperm(n, device="cuda", generator=g)
+                us, ts = u[perm].contiguous(), t[perm].contiguous()
+                pos = 0
+            ub, tb = us[pos:pos + batch], ts[pos:pos + batch]
+            pos += batch
+            sans.sans_mlp_forward(self.wb, ub, y, ws)
+            sans.sans_mse_grad(y, tb, dy, loss)
+            sans.sans_mlp_backward(self.wb, ub, dy, self.dw, ws)
+            self.step_count += 1
+            cur = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * k / max(steps, 1)))
+            sans.sans_adam_step(self.w32, self.wb, self.dw, self.m, self.v, cur, self.step_count)
+            if log_every and (k + 1) % log_every == 0:
+                hist.append((k + 1, float(loss) / log_every, time.perf_counter() - t0))
+                loss.zero_()
+        torch.cuda.synchronize()
+        return hist
+
+    def attach(self, model_handle) -> None:
+        lo = (sans.C.c_float * 4)(*self.lo)
+        hi = (sans.C.c_float * 4)(*self.hi)
+        rc = sans.lib.sans_model_attach_surrogate(model_handle, sans.C.c_void_p(self.wb.data_ptr()), lo, hi)
+        if rc != 0:
+            raise sans.SansError(rc, "sans_model_attach_surrogate", sans.lib.sans_last_error().decode())

@@ -190,3 +190,54 @@ def batch_experiments(n_exp: int = 4096, seed: int = 4096, nx: int = 128,
                    nx=nx, ny=nx)
         out.append(dict(exp_id=e, n=n, seed=5, params=p))
     return out
+
+
+# --------------------------------------------------------------------------
+# The learned surrogate: training inputs and their box.
+#
+# Physical inputs x = (ln(q s0), ln(s1/s0), ln(s2/s0), poly, 0, 0, 0, 0):
+#   parallelepiped: s0 = A (edge), B/A and C/A uniform in [1, 10], no
+#                   polydispersity (orientation average 76 x 76);
+#   spheroid:       ellipsoid of revolution a = b = s0, c/a uniform in
+#                   [1, 10], Schulz width uniform in [0, 0.3] on all axes
+#                   (orientation x size average 76 x 76).
+# q s0 log-uniform in [1e-3, 20].
+SURROGATE_BOX = {
+    "parallelepiped": ((math.log(1e-3), 0.0, 0.0, 0.0), (math.log(20.0), math.log(10.0), math.log(10.0), 0.0)),
+    "spheroid": ((math.log(1e-3), 0.0, 0.0, 0.0), (math.log(20.0), 0.0, math.log(10.0), 0.3)),
+}
+
+
+def surrogate_inputs(model: str, n: int, seed: int) -> np.ndarray:
+    """Seeded training/validation inputs [n, 8] (float32) in the box."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi = SURROGATE_BOX[model]
+    x = np.zeros((n, 8), dtype=np.float64)
+    x[:, 0] = rng.uniform(lo[0], hi[0], size=n)
+    if model == "parallelepiped":
+        x[:, 1] = np.log(rng.uniform(1.0, 10.0, size=n))
+        x[:, 2] = np.log(rng.uniform(1.0, 10.0, size=n))
+    else:
+        x[:, 2] = np.log(rng.uniform(1.0, 10.0, size=n))
+        x[:, 3] = rng.uniform(0.0, 0.3, size=n)
+    return x.astype(np.float32)
+
+
+def surrogate_parallelepiped() -> dict:
+    """Tracing workload of the surrogate: isotropic parallelepipeds
+    20 x 40 x 120 A, 128x128 detector (as quad_parallelepiped)."""
+    wl = quad_parallelepiped()
+    wl["name"] = "surrogate_parallelepiped"
+    wl["params"] = dict(wl["params"], mode="surrogate")
+    return wl
+
+
+def surrogate_spheroid() -> dict:
+    wl = quad_spheroid()
+    wl["name"] = "surrogate_spheroid"
+    wl["params"] = dict(wl["params"], mode="surrogate")
+    return wl
+
+
+WORKLOADS["surrogate_parallelepiped"] = surrogate_parallelepiped
+WORKLOADS["surrogate_spheroid"] = surrogate_spheroid
