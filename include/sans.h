@@ -254,7 +254,9 @@ int sans_model_constants(sans_model_t m, double* out3);
  * b1[256] W2 b2 W3 b3 W4[256] b4[1], W_l stored [in][out].  "w_bf16" is that
  * vector in BF16 (device), "w32" in FP32.  All matrix products are BF16 MFMA
  * (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; operands are rounded to
- * BF16 (round to nearest even) when they are loaded.
+ * BF16 (round to nearest even) when they are loaded, except the 8 inputs of
+ * the first layer, which enter as two BF16 parts hi = bf16(x) and
+ * lo = bf16(x - hi), both multiplied by W0 (16 bits of input precision).
  * ------------------------------------------------------------------------- */
 
 /* Number of parameters (199,937). */
@@ -294,15 +296,19 @@ const char* sans_mlp_last_error(void);
  * domain_lo/hi: host float[4], the training box of the physical inputs
  * x = (ln(q size[0]), ln(size[1]/size[0]), ln(size[2]/size[0]), poly); the
  * network sees u_k = (2 x_k - lo_k - hi_k)/(hi_k - lo_k) (0 where lo_k = hi_k).
- * Tracing then weights a neutron by <F^2>(0) exp(net(u)) in place of the
- * quadrature average <F^2>(q) of SANS_MODE_QUAD; neutrons whose q falls
+ * Tracing then weights a neutron by <F^2>(0) P_ref(q) exp(net(u)) in place
+ * of the quadrature average <F^2>(q) of SANS_MODE_QUAD, with the reference
+ * curve P_ref = (1 + q^2 Rg^2/6)^-2, Rg^2 = (s0^2 + s1^2 + s2^2)/12 for the
+ * parallelepiped and /5 for the ellipsoid (it has the Guinier and the q^-4
+ * limits; the network learns the rest); neutrons whose q falls
  * outside the box are queued and traced again with the exact quadrature (no
  * divergent branch in the network kernel).  A model whose own shape lies
  * outside the box is traced with the exact quadrature throughout. */
 int sans_model_attach_surrogate(sans_model_t m, const void* w_bf16, const float* domain_lo,
                                 const float* domain_hi);
 
-/* Training targets: out[i] = ln(<F^2>(q) / <F^2>(0)) of an isotropically
+/* Training targets: out[i] = ln(<F^2>(q) / <F^2>(0)) - ln P_ref(q) (P_ref as
+ * for sans_model_attach_surrogate) of an isotropically
  * oriented particle (kind SANS_ELLIPSOID: of revolution, 1D orientation
  * average; SANS_PARALLELEPIPED: 2D) for physical inputs x[i][8] =
  * (ln(q s0), ln(s1/s0), ln(s2/s0), poly, 0, 0, 0, 0) (device FP32), with

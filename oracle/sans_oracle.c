@@ -900,11 +900,15 @@ void orc_mlp_forward(const double* w, const double* x, int32_t n, double* y, int
     double* a = (double*)malloc(sizeof(double) * ORC_NH);
     double* b = (double*)malloc(sizeof(double) * ORC_NH);
     for (int i = 0; i < n; ++i) {
-        /* layer 0 */
+        /* layer 0: with operand rounding, each input enters as the sum of
+         * its two BF16 parts, hi = bf16(x) and lo = bf16(x - hi) */
         for (int o = 0; o < ORC_NH; ++o) {
             double s = 0.0;
-            for (int k = 0; k < ORC_NIN; ++k)
-                s += op(x[(long)i * ORC_NIN + k], round_bf16) * op(w[orc_offw(0) + (long)k * ORC_NH + o], round_bf16);
+            for (int k = 0; k < ORC_NIN; ++k) {
+                const double xv = x[(long)i * ORC_NIN + k];
+                const double xin = round_bf16 ? orc_bf16_round(xv) + orc_bf16_round(xv - orc_bf16_round(xv)) : xv;
+                s += xin * op(w[orc_offw(0) + (long)k * ORC_NH + o], round_bf16);
+            }
             double zz = s + op(w[orc_offb(0) + o], round_bf16);
             if (z) z[(long)i * ORC_NH + o] = zz;
             a[o] = orc_silu(zz);
@@ -991,11 +995,14 @@ void orc_mlp_backward(const double* w, const double* x, const double* dy, int32_
 }
 
 /* ------------------------------------------------------------------------ */
-/* Surrogate mode: the weight uses <F^2>(0) exp(net(u)) with the network's
- * inputs u_k = (2 x_k - lo_k - hi_k)/(hi_k - lo_k) (0 where lo_k = hi_k) of
- * x = (ln(q s0), ln(s1/s0), ln(s2/s0), p); outside the box the exact average
- * is used.  The network runs with BF16 operand rounding (the device's
- * operand precision).  <F^2>(0) is the exact average at q = 0.           */
+/* Surrogate mode: the weight uses <F^2>(0) P_ref(q) exp(net(u)) with the
+ * network's inputs u_k = (2 x_k - lo_k - hi_k)/(hi_k - lo_k) (0 where lo_k =
+ * hi_k) of x = (ln(q s0), ln(s1/s0), ln(s2/s0), p) and the reference
+ * P_ref = (1 + q^2 Rg^2/6)^-2, Rg^2 = (s0^2 + s1^2 + s2^2)/12 for the
+ * parallelepiped and /5 for the ellipsoid (its Guinier and Porod limits);
+ * outside the box the exact average is used.  The network runs with BF16
+ * operand rounding (the device's operand precision).  <F^2>(0) is the exact
+ * average at q = 0.                                                       */
 static double g_sur_w[ORC_NP];
 static double g_sur_lo[4], g_sur_hi[4];
 static int g_sur_set = 0;
@@ -1029,5 +1036,8 @@ static double surrogate_f2(const orc_params* p, double q, int* in_domain)
     orc_params p0 = *p;
     p0.mode = 1;
     double f2_0 = pq_avg_nodes(&p0, 0.0, qv0, gx, gw);
-    return f2_0 * exp(y);
+    const double rg2 = (p->size[0] * p->size[0] + p->size[1] * p->size[1] + p->size[2] * p->size[2])
+                     / (p->kind == 4 ? 12.0 : 5.0);
+    const double t = 1.0 + q * q * rg2 / 6.0;
+    return f2_0 * exp(y) / (t * t);
 }

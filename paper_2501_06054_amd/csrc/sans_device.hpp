@@ -121,6 +121,37 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     return U4{c0, c1, c2, c3};
 }
 
+// FP64 reciprocal, quotient and square root for finite, normal operands of
+// the geometry: the hardware estimates (v_rcp_f64, v_rsq_f64) refined by
+// Newton steps to about one ulp, without the scaling and special-case
+// handling of the IEEE sequences (none of these operands is zero, denormal
+// or infinite; a zero divisor gives a NaN, which fails every comparison).
+__device__ __forceinline__ double rcp_d(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ double div_d(double a, double b)
+{
+    const double r = rcp_d(b);
+    const double q = a * r;
+    return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+}
+// x > 0
+__device__ __forceinline__ double sqrt_d(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double e = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, e, g);
+    h = __builtin_fma(h, e, h);
+    const double d = __builtin_fma(-g, g, x);
+    return __builtin_fma(d, h, g);
+}
+
 // (x + 1/2) 2^-32 - 1/2 and (x + 1/2) 2^-32, exact in FP64.
 __device__ __forceinline__ double centred_u(uint32_t x)
 {
@@ -519,11 +550,11 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     const double sx = centred_u(r0.x) * a.src_w, sy = centred_u(r0.y) * a.src_h;
     const double tx = centred_u(r0.z) * a.slit_w, ty = centred_u(r0.w) * a.slit_h;
     const double dx = tx - sx, dy = ty - sy, dz = a.slit_z - a.src_z;
-    const double dl = sqrt(dx * dx + dy * dy + dz * dz);
-    const double idl = 1.0 / dl;
+    const double dl = sqrt_d(dx * dx + dy * dy + dz * dz);
+    const double idl = rcp_d(dl);
     const double kx = dx * idl, ky = dy * idl, kz = dz * idl;
     const double lambda = __builtin_fma(a.lambda_span, 2.0 * u64(r1.x) - 1.0, a.lambda0);
-    const double k = 2.0 * kPi / lambda;
+    const double k = div_d(2.0 * kPi, lambda);
 
     // slab entry/exit along src + s k, s >= 0
     double s_in = 0.0, s_out = 1e300;
@@ -534,7 +565,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             if (dv[c] != 0.0) {
-                const double inv = 1.0 / dv[c];
+                const double inv = rcp_d(dv[c]);
                 const double t1 = (-h[c] - o[c]) * inv, t2 = (h[c] - o[c]) * inv;
                 s_in = fmax(s_in, fmin(t1, t2));
                 s_out = fmin(s_out, fmax(t1, t2));
@@ -554,23 +585,23 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     // cone sampling about the flight direction; basis of Duff et al. (JCGT 2017)
     const double t = u64(r1.z) * a.omc;
     const double c2 = 1.0 - t;
-    const double s2 = sqrt(t * (2.0 - t));
+    const double s2 = sqrt_d(t * (2.0 - t));
     double sps, cps;
     sincospi(2.0 * u64(r1.w), &sps, &cps);
     const double sg = kz >= 0.0 ? 1.0 : -1.0;
-    const double aa = -1.0 / (sg + kz);
+    const double aa = -rcp_d(sg + kz);
     const double bb = kx * ky * aa;
     const double px = cps * (1.0 + sg * kx * kx * aa) + sps * bb;
     const double py = cps * (sg * bb) + sps * (sg + ky * ky * aa);
     const double pz = cps * (-sg * kx) + sps * (-ky);
     const double fx = c2 * kx + s2 * px, fy = c2 * ky + s2 * py, fz = c2 * kz + s2 * pz;
-    const double qd = k * sqrt(2.0 * t);
+    const double qd = k * sqrt_d(2.0 * t);
     const float q = (float)qd;
     ev.q = in_sample ? q : 0.0f;
 
     // detector plane and pixel
     const bool forward = fz > 0.0;
-    const double sd = (a.det_z - rz) / fz;
+    const double sd = div_d(a.det_z - rz, fz);
     const double xd = __builtin_fma(sd, fx, rx), yd = __builtin_fma(sd, fy, ry);
     const double fxp = floor((xd + a.det_hw) * a.inv_px);
     const double fyp = floor((yd + a.det_hh) * a.inv_py);

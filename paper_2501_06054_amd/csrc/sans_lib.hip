@@ -154,29 +154,31 @@ __global__ void k_reduce_partials(double* det, const double* partial, int G, int
     det[p] = accumulate ? det[p] + s : s;
 }
 
-// Binned tally, pass 1: the events of one chunk of neutrons go to the bucket
-// of their detector tile (rows [t*rows, (t+1)*rows)).  Space in a bucket is
-// reserved once per workgroup iteration (one integer atomic per tile), ranks
-// inside the workgroup come from LDS counters.  An event is (pixel within
-// the tile, FP32 weight bits).
+// Binned tally, pass 1: the events of one chunk of neutrons go to the
+// bucket of their detector tile (rows [t*rows, (t+1)*rows)).  Every wave owns
+// one private segment per tile, so no two waves ever write the same
+// counter: ranks come from ballots, and lane t of the wave keeps the running
+// count of tile t in a register (ntiles <= 64).  At the end each wave stores
+// its per-tile counts.  An event is (pixel within the tile, FP32 weight bits).
 constexpr int kEmitBlock = 256;
 constexpr int kMaxTiles = 64;
 
 template <int KIND, int MODE>
 __global__ __launch_bounds__(kEmitBlock) void k_emit(const TraceArgs a, LdsLayout lay, uint2* buckets,
-                                                     unsigned* bucket_count, unsigned cap,
-                                                     int tile_pixels, int ntiles)
+                                                     unsigned* seg_count, unsigned capw, int tile_pixels,
+                                                     int ntiles)
 {
     extern __shared__ double lds_d[];
-    __shared__ unsigned cnt[kMaxTiles], base[kMaxTiles];
     const LdsPtrs lp = stage_all(a, lay, lds_d);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const unsigned nwaves = gridDim.x * (kEmitBlock / 64);
+    const unsigned wv = blockIdx.x * (kEmitBlock / 64) + (threadIdx.x >> 6);
+    unsigned count = 0;  // lane t: events of tile t so far
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < a.n; j0 += stride) {
-        if (threadIdx.x < ntiles) cnt[threadIdx.x] = 0u;
-        __syncthreads();
-        const uint64_t j = j0 + threadIdx.x;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j - threadIdx.x < a.n; j += stride) {
         int t = -1;
-        unsigned rank = 0, local = 0;
+        unsigned local = 0;
         float w = 0.0f;
         if (j < a.n) {
             const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
@@ -184,38 +186,50 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const TraceArgs a, LdsLayou
                 t = ev.pixel / tile_pixels;
                 local = (unsigned)(ev.pixel - t * tile_pixels);
                 w = ev.w;
-                rank = atomicAdd(&cnt[t], 1u);
             }
         }
-        __syncthreads();
-        if (threadIdx.x < ntiles) {
-            const unsigned c = cnt[threadIdx.x];
-            base[threadIdx.x] = c ? atomicAdd(bucket_count + threadIdx.x, c) : 0u;
+        // one round per distinct tile among the wave's events (wave-uniform
+        // control flow: the tile, its base and the ballots are scalars)
+        uint64_t pending = __ballot(t >= 0);
+        while (pending) {
+            const int tt = __builtin_amdgcn_readlane(t, (int)__builtin_ctzll(pending));
+            const uint64_t same = __ballot(t == tt);
+            const unsigned base = (unsigned)__builtin_amdgcn_readlane((int)count, tt);
+            if (t == tt) {
+                const unsigned rank = base + __builtin_amdgcn_mbcnt_hi((unsigned)(same >> 32),
+                                                                       __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
+                buckets[((size_t)tt * nwaves + wv) * capw + rank] = make_uint2(local, __float_as_uint(w));
+            }
+            if (lane == tt) count += (unsigned)__builtin_popcountll(same);
+            pending &= ~same;
         }
-        __syncthreads();
-        if (t >= 0) buckets[(size_t)t * cap + base[t] + rank] = make_uint2(local, __float_as_uint(w));
     }
+    if (lane < ntiles) seg_count[(size_t)lane * nwaves + wv] = count;
 }
 
-// Binned tally, pass 2: workgroup (t, s) accumulates slice s of bucket t in
-// an LDS histogram of tile t and adds it to its own partial slot.
-__global__ __launch_bounds__(kHistBlock) void k_bin_accumulate(const uint2* buckets,
-                                                               const unsigned* bucket_count,
-                                                               unsigned cap, int tile_pixels,
+// Binned tally, pass 2: workgroup (t, s) sums the segments of waves
+// [s W/S, (s+1) W/S) of tile t in an LDS histogram of the tile (each of its
+// waves takes every 16th segment) and adds it to its own partial slot.
+__global__ __launch_bounds__(kHistBlock) void k_bin_accumulate(const uint2* buckets, const unsigned* seg_count,
+                                                               unsigned capw, unsigned nwaves, int tile_pixels,
                                                                int slices, double* partial)
 {
     extern __shared__ double hist[];
     const int t = blockIdx.x / slices, sl = blockIdx.x % slices;
     for (int i = threadIdx.x; i < tile_pixels; i += blockDim.x) hist[i] = 0.0;
     __syncthreads();
-    const unsigned nt = bucket_count[t];
-    const unsigned lo = (unsigned)((uint64_t)nt * sl / slices);
-    const unsigned hi = (unsigned)((uint64_t)nt * (sl + 1) / slices);
-    const uint2* b = buckets + (size_t)t * cap;
-    for (unsigned i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const uint2 e = b[i];
-        __hip_atomic_fetch_add(hist + e.x, (double)__uint_as_float(e.y), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    const unsigned w0 = (unsigned)((uint64_t)nwaves * sl / slices);
+    const unsigned w1 = (unsigned)((uint64_t)nwaves * (sl + 1) / slices);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (unsigned w = w0 + wave; w < w1; w += kHistBlock / 64) {
+        const size_t seg = (size_t)t * nwaves + w;
+        const unsigned cnt = seg_count[seg];
+        const uint2* b = buckets + seg * capw;
+        for (unsigned i = lane; i < cnt; i += 64) {
+            const uint2 e = b[i];
+            __hip_atomic_fetch_add(hist + e.x, (double)__uint_as_float(e.y), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
     }
     __syncthreads();
     double* out = partial + (size_t)blockIdx.x * tile_pixels;
@@ -466,6 +480,10 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
 }
 
 // ------------------------------------------------------------------ surrogate mode
+// Rg^2 = (s0^2 + s1^2 + s2^2) / D: D = 12 for the parallelepiped (edges), 5
+// for the ellipsoid (semi-axes).
+__host__ __device__ constexpr double sur_rg2_scale(int kind) { return kind == kParallelepiped ? 1.0 / 12.0 : 1.0 / 5.0; }
+
 // Inputs of the network for one neutron: ln(q s0), ln(s1/s0), ln(s2/s0), p.
 struct SurConst {
     float ls0;            // ln(size[0])
@@ -473,6 +491,7 @@ struct SurConst {
     float lo0, hi0;       // domain of ln(q s0)
     float mid0, scale0;   // normalisation of ln(q s0): (x - mid0) * scale0
     float f2_0;           // <F^2>(0)
+    float kref;           // Rg^2 / 6 (A^2): P_ref = (1 + q^2 kref)^-2
 };
 
 // Surrogate tracer.  Geometry and S(q) per lane; the network per wave (16
@@ -487,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const m
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     float* xs = xs_all[wave];
     const __amdgpu_buffer_rsrc_t rp = sur::make_rsrc(pk, (int)(16 * sur::kPackTotal));
-    const __amdgpu_buffer_rsrc_t rw = sur::make_rsrc(wts, (int)(2 * mlp::kParams));
+    const __amdgpu_buffer_rsrc_t rw = sur::make_rsrc(wts, (int)(2 * sur::kWeightsPadded));
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < a.n; j0 += stride) {
         const uint64_t j = j0 + threadIdx.x;
@@ -514,7 +533,8 @@ __global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const m
         }
         __syncthreads();
         if (in_dom) {
-            const double w = (double)(ev.w * sc.f2_0 * __expf(y));
+            const float t = __builtin_fmaf(ev.q * ev.q, sc.kref, 1.0f);
+            const double w = (double)(ev.w * sc.f2_0 * __expf(y) * rcpf(t * t));
             __hip_atomic_fetch_add(det + ev.pixel, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else if (valid && ev.pixel >= 0) {
             const unsigned slot = atomicAdd(qcount, 1u);
@@ -608,7 +628,11 @@ __global__ __launch_bounds__(kBlock) void k_pq_dataset(const TraceArgs a, const 
         wsum += wy;
     }
     (void)wsum;
-    out[idx] = (float)log(num / den);
+    // the network's target: ln of the normalised average minus ln P_ref,
+    // P_ref = (1 + (q Rg)^2 / 6)^-2 with the body's Rg^2 (Guinier at small q,
+    // q^-4 at large q), which takes most of the dynamic range off the network
+    const double rg2 = (1.0 + exp(2.0 * (double)xi[1]) + exp(2.0 * (double)xi[2])) * sur_rg2_scale(KIND);
+    out[idx] = (float)(log(num / den) + 2.0 * log1p(exp(2.0 * (double)xi[0]) * rg2 / 6.0));
 }
 
 // ------------------------------------------------------------------ dispatch tables
@@ -721,7 +745,8 @@ struct sans_model_s {
     size_t partial_cap = 0;     // doubles
     uint2* d_buckets = nullptr;
     size_t bucket_cap = 0;      // events
-    unsigned* d_bucket_count = nullptr;
+    unsigned* d_bucket_count = nullptr;  // [tile][wave] event counts
+    size_t bucket_count_cap = 0;
     // surrogate network (SANS_MODE_SURROGATE)
     double sur_f2_0 = 0.0;      // <F^2>(q = 0) from the size nodes (normalisation of the target)
     __bf16* d_sur_w = nullptr;  // flat BF16 parameters
@@ -1133,6 +1158,9 @@ bool surrogate_inputs(const sans_model_s* m, SurConst& sc)
     sc.mid0 = 0.5f * (sc.lo0 + sc.hi0);
     sc.scale0 = sc.hi0 > sc.lo0 ? 2.0f / (sc.hi0 - sc.lo0) : 0.0f;
     sc.f2_0 = (float)m->sur_f2_0;
+    const int kind = p.kind == SANS_PARALLELEPIPED ? kParallelepiped : kEllipsoid;
+    sc.kref = (float)((p.size[0] * p.size[0] + p.size[1] * p.size[1] + p.size[2] * p.size[2])
+                      * sur_rg2_scale(kind) / 6.0);
     return true;
 }
 
@@ -1305,16 +1333,19 @@ int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uin
         const int ntiles = (m->p.ny + rows - 1) / rows;
         const int tile_pixels = rows * m->p.nx;
         const int slices = std::max(1, m->num_cu / ntiles);
-        const uint64_t chunk = std::min<uint64_t>(n, std::max<uint64_t>(1u << 20, (1ull << 27) / ntiles));
+        // one chunk writes at most 2^28 / ntiles bytes of events (8 B each):
+        // small enough to be read back from the 256 MB last-level cache
+        const uint64_t chunk = std::min<uint64_t>(n, std::max<uint64_t>(1u << 20, (1ull << 25) / ntiles));
+        // the emit grid and each wave's segment capacity (its neutrons per chunk)
+        const uint64_t eblocks = std::max<uint64_t>(
+            1, std::min<uint64_t>((chunk + kEmitBlock - 1) / kEmitBlock, (uint64_t)m->num_cu * 8));
+        const unsigned nwaves = (unsigned)eblocks * (kEmitBlock / 64);
+        const uint64_t iters = (chunk + eblocks * kEmitBlock - 1) / (eblocks * kEmitBlock);
+        const unsigned capw = (unsigned)(iters * 64);
         int rc;
         if ((rc = ensure(m->d_partial, m->partial_cap, (size_t)ntiles * slices * tile_pixels))) return rc;
-        if ((rc = ensure(m->d_buckets, m->bucket_cap, (size_t)ntiles * chunk))) return rc;
-        if (!m->d_bucket_count) {
-            if (hipMalloc(&m->d_bucket_count, sizeof(unsigned) * kMaxTiles) != hipSuccess) {
-                m->d_bucket_count = nullptr;
-                return fail(SANS_E_NOMEM, "workspace allocation failed");
-            }
-        }
+        if ((rc = ensure(m->d_buckets, m->bucket_cap, (size_t)ntiles * nwaves * capw))) return rc;
+        if ((rc = ensure(m->d_bucket_count, m->bucket_count_cap, (size_t)ntiles * nwaves))) return rc;
         if ((rc = launch_fill(m->d_partial, (size_t)ntiles * slices * tile_pixels, s))) return rc;
         const LdsLayout lay = layout(m, false);
         const size_t shmem = lds_bytes(lay);
@@ -1325,17 +1356,12 @@ int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uin
             TraceArgs ac = a;
             ac.first = first + c0;
             ac.n = std::min<uint64_t>(chunk, n - c0);
-            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kMaxTiles), 0, s, m->d_bucket_count, kMaxTiles);
-            HIP_TRY(hipGetLastError());
-            const uint64_t blocks_needed = (ac.n + kEmitBlock - 1) / kEmitBlock;
-            const unsigned egrid = (unsigned)std::max<uint64_t>(
-                1, std::min<uint64_t>(blocks_needed, (uint64_t)m->num_cu * 8));
-            hipLaunchKernelGGL(efn, dim3(egrid), dim3(kEmitBlock), shmem, s, ac, lay, m->d_buckets,
-                               m->d_bucket_count, (unsigned)chunk, tile_pixels, ntiles);
+            hipLaunchKernelGGL(efn, dim3((unsigned)eblocks), dim3(kEmitBlock), shmem, s, ac, lay, m->d_buckets,
+                               m->d_bucket_count, capw, tile_pixels, ntiles);
             HIP_TRY(hipGetLastError());
             hipLaunchKernelGGL(k_bin_accumulate, dim3((unsigned)(ntiles * slices)), dim3(kHistBlock),
-                               sizeof(double) * tile_pixels, s, m->d_buckets, m->d_bucket_count,
-                               (unsigned)chunk, tile_pixels, slices, m->d_partial);
+                               sizeof(double) * tile_pixels, s, m->d_buckets, m->d_bucket_count, capw, nwaves,
+                               tile_pixels, slices, m->d_partial);
             HIP_TRY(hipGetLastError());
         }
         hipLaunchKernelGGL(k_reduce_binned, dim3(fill_grid), dim3(256), 0, s, det, m->d_partial,
@@ -1459,7 +1485,10 @@ int sans_model_attach_surrogate(sans_model_t m, const void* w_bf16, const float*
     if (!m || !w_bf16 || !domain_lo || !domain_hi) return fail(SANS_E_INVALID_ARG, "NULL argument");
     for (int k = 0; k < 4; ++k)
         if (!(domain_hi[k] >= domain_lo[k])) return fail(SANS_E_INVALID_ARG, "domain_hi < domain_lo");
-    if (!m->d_sur_w) HIP_TRY(hipMalloc(&m->d_sur_w, sizeof(__bf16) * mlp::kParams));
+    if (!m->d_sur_w) {
+        HIP_TRY(hipMalloc(&m->d_sur_w, sizeof(__bf16) * sur::kWeightsPadded));
+        HIP_TRY(hipMemset(m->d_sur_w, 0, sizeof(__bf16) * sur::kWeightsPadded));
+    }
     if (!m->d_sur_pack) HIP_TRY(hipMalloc(&m->d_sur_pack, sizeof(mlp::bf16x8) * sur::kPackTotal));
     HIP_TRY(hipMemcpy(m->d_sur_w, w_bf16, sizeof(__bf16) * mlp::kParams, hipMemcpyDeviceToDevice));
     hipLaunchKernelGGL(sur::k_pack_surrogate, dim3((unsigned)((sur::kPackTotal + 255) / 256)), dim3(256), 0,

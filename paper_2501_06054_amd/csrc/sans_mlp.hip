@@ -4,6 +4,7 @@
 // hand-written BF16 MFMA GEMM (k_gemm) with FP32 accumulation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 
 #include "../../include/sans.h"
@@ -21,12 +22,18 @@ int mfail(int status, const std::string& msg)
     return status;
 }
 
-template <bool AT, bool BT, typename TA, typename TB, int EPI>
+template <bool AT, bool BT, typename TA, typename TB, int EPI, bool SPLIT = false>
 int gemm(int M, int N, int K, const TA* A, int lda, const TB* B, int ldb, float* C, int ldc,
          const TB* bias, float* aux, hipStream_t s)
 {
-    const dim3 grid((unsigned)((N + kTN - 1) / kTN), (unsigned)((M + kTM - 1) / kTM));
-    hipLaunchKernelGGL((k_gemm<AT, BT, TA, TB, EPI>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
+    // split-K for the atomic epilogue: about 512 workgroups, >= 256 of K each
+    unsigned splits = 1;
+    if (EPI == kEpiAtomic) {
+        const unsigned tiles = (unsigned)(((N + kTN - 1) / kTN) * ((M + kTM - 1) / kTM));
+        splits = std::max(1u, std::min((unsigned)(K / 256), 512u / std::max(1u, tiles)));
+    }
+    const dim3 grid((unsigned)((N + kTN - 1) / kTN), (unsigned)((M + kTM - 1) / kTM), splits);
+    hipLaunchKernelGGL((k_gemm<AT, BT, TA, TB, EPI, SPLIT>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C,
                        ldc, bias, aux);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mfail(SANS_E_HIP, std::string("gemm: ") + hipGetErrorString(e));
@@ -35,7 +42,8 @@ int gemm(int M, int N, int K, const TA* A, int lda, const TB* B, int ldb, float*
 
 int colsum(const float* X, int M, int N, float* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, X, M, N, out);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((N + 255) / 256), (unsigned)((M + 255) / 256)), dim3(256), 0, s,
+                       X, M, N, out);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mfail(SANS_E_HIP, std::string("colsum: ") + hipGetErrorString(e));
     return SANS_OK;
@@ -66,8 +74,8 @@ int sans_mlp_forward(const void* w_bf16, const float* x, int64_t n, float* y, vo
     float* W = (float*)ws;
     const int N = (int)n;
     int rc;
-    // Z0 = X W0 + b0, H0 = silu(Z0)
-    if ((rc = gemm<false, false, float, __bf16, kEpiBiasSilu>(N, kHid, kIn, x, kIn, w + offW(0), kHid,
+    // Z0 = (hi(X) + lo(X)) W0 + b0, H0 = silu(Z0)
+    if ((rc = gemm<false, false, float, __bf16, kEpiBiasSilu, true>(N, kHid, 2 * kIn, x, kIn, w + offW(0), kHid,
                                                                ws_z(W, n, 0), kHid, w + offB(0),
                                                                ws_h(W, n, 0), s)))
         return rc;
@@ -92,8 +100,10 @@ int sans_mlp_backward(const void* w_bf16, const float* x, const float* dy, int64
     float* W = (float*)ws;
     const int N = (int)n;
     int rc;
+    // every gradient is accumulated (split-K and column-sum atomics)
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)((kParams + 255) / 256)), dim3(256), 0, s, dw, kParams);
     // output layer: dW4 = H3^T dy, db4 = sum dy
-    if ((rc = gemm<true, false, float, float, kEpiStore>(kHid, 1, N, ws_h(W, n, 3), kHid, dy, 1,
+    if ((rc = gemm<true, false, float, float, kEpiAtomic>(kHid, 1, N, ws_h(W, n, 3), kHid, dy, 1,
                                                           dw + kOffW4, 1, nullptr, nullptr, s)))
         return rc;
     if ((rc = colsum(dy, N, 1, dw + kOffB4, s))) return rc;
@@ -106,7 +116,7 @@ int sans_mlp_backward(const void* w_bf16, const float* x, const float* dy, int64
         const float* hin = l == 0 ? x : ws_h(W, n, l - 1);
         const int kin = l == 0 ? kIn : kHid;
         // dW_l = H_{l-1}^T dZ_l, db_l = colsum(dZ_l)
-        if ((rc = gemm<true, false, float, float, kEpiStore>(kin, kHid, N, hin, kin, g, kHid, dw + offW(l),
+        if ((rc = gemm<true, false, float, float, kEpiAtomic>(kin, kHid, N, hin, kin, g, kHid, dw + offW(l),
                                                               kHid, nullptr, nullptr, s)))
             return rc;
         if ((rc = colsum(g, N, kHid, dw + offB(l), s))) return rc;

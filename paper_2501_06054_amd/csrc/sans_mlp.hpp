@@ -6,7 +6,9 @@
 //   W0[8][256] b0[256] W1[256][256] b1[256] W2[256][256] b2[256]
 //   W3[256][256] b3[256] W4[256] b4[1]                (199,937 values)
 // W_l is stored [in][out] row-major.  Matrix products use
-// v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation.
+// v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation.  The inputs of
+// the first layer enter as two BF16 parts, hi = bf16(x) and lo = bf16(x -
+// hi), both multiplied by W0 (16 bits of input precision instead of 8).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -53,11 +55,19 @@ enum : int {
     kEpiBiasSilu = 1,   // Z = acc + bias[n] -> C (pre-activation), H = silu(Z) -> aux
     kEpiBias = 2,       // C = acc + bias[n]
     kEpiSiluGrad = 3,   // C = acc * silu'(aux[m][n])  (aux = pre-activation)
+    kEpiAtomic = 4,     // C += acc (FP32 atomics; split-K over blockIdx.z)
 };
 
 constexpr int kTM = 64, kTN = 64, kTK = 32;
 
-template <bool A_T, bool B_T, typename TA, typename TB, int EPI>
+// The two BF16 parts of an FP32 value.
+__device__ __forceinline__ __bf16 bf16_hi(float x) { return (__bf16)x; }
+__device__ __forceinline__ __bf16 bf16_lo(float x) { return (__bf16)(x - (float)(__bf16)x); }
+
+// SPLIT (first layer, A = X not transposed): K = 2 * lda; A(m, k) is the hi
+// part of X[m][k] for k < lda and the lo part of X[m][k - lda] above, and
+// B(k, n) = B[k mod lda][n].
+template <bool A_T, bool B_T, typename TA, typename TB, int EPI, bool SPLIT = false>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __restrict__ A, int lda,
                                               const TB* __restrict__ B, int ldb, float* __restrict__ C,
                                               int ldc, const TB* __restrict__ bias,
@@ -77,7 +87,14 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    for (int k0 = 0; k0 < K; k0 += kTK) {
+    // split-K (kEpiAtomic): workgroup z takes K range [z*ks, (z+1)*ks)
+    int kbeg = 0, kend = K;
+    if constexpr (EPI == kEpiAtomic) {
+        const int ks = ((K + gridDim.z - 1) / gridDim.z + kTK - 1) / kTK * kTK;
+        kbeg = blockIdx.z * ks;
+        kend = min(K, kbeg + ks);
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += kTK) {
         // each thread stages 8 elements of A and 8 of B
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -85,14 +102,24 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
             int mm, kk;
             if (A_T) { kk = idx / kTM; mm = idx % kTM; } else { mm = idx / kTK; kk = idx % kTK; }
             const int gm = m0 + mm, gk = k0 + kk;
-            float v = 0.0f;
-            if (gm < M && gk < K) v = to_f(A_T ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]);
-            As[mm][kk] = (__bf16)v;
+            if constexpr (SPLIT) {
+                __bf16 v = (__bf16)0.0f;
+                if (gm < M && gk < kend) {
+                    const float x = to_f(A[(int64_t)gm * lda + (gk < lda ? gk : gk - lda)]);
+                    v = gk < lda ? bf16_hi(x) : bf16_lo(x);
+                }
+                As[mm][kk] = v;
+            } else {
+                float v = 0.0f;
+                if (gm < M && gk < kend) v = to_f(A_T ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]);
+                As[mm][kk] = (__bf16)v;
+            }
             int nn, kb;
             if (B_T) { nn = idx / kTK; kb = idx % kTK; } else { kb = idx / kTN; nn = idx % kTN; }
             const int gn = n0 + nn, gkb = k0 + kb;
             float u = 0.0f;
-            if (gn < N && gkb < K) u = to_f(B_T ? B[(int64_t)gn * ldb + gkb] : B[(int64_t)gkb * ldb + gn]);
+            const int bk = SPLIT && gkb >= K / 2 ? gkb - K / 2 : gkb;
+            if (gn < N && gkb < kend) u = to_f(B_T ? B[(int64_t)gn * ldb + bk] : B[(int64_t)bk * ldb + gn]);
             Bs[nn][kb] = (__bf16)u;
         }
         __syncthreads();
@@ -126,6 +153,8 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
                 const int64_t o = (int64_t)m * ldc + n;
                 if constexpr (EPI == kEpiStore) {
                     C[o] = v;
+                } else if constexpr (EPI == kEpiAtomic) {
+                    __hip_atomic_fetch_add(C + o, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } else if constexpr (EPI == kEpiBias) {
                     C[o] = v + to_f(bias[n]);
                 } else if constexpr (EPI == kEpiBiasSilu) {
@@ -138,14 +167,23 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
             }
 }
 
-// Column sums: out[n] = sum_m X[m][n]  (bias gradients).
+// Column sums: out[n] += sum_m X[m][n] (bias gradients); workgroup (x, y)
+// sums rows [256 y, 256 y + 256) of columns [256 x, 256 x + 256) and adds
+// the result atomically (out cleared beforehand).
 static __global__ void k_colsum(const float* __restrict__ X, int M, int N, float* __restrict__ out)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
+    const int m0 = blockIdx.y * 256, m1 = min(M, m0 + 256);
     float s = 0.0f;
-    for (int m = 0; m < M; ++m) s += X[(int64_t)m * N + n];
-    out[n] = s;
+    for (int m = m0; m < m1; ++m) s += X[(int64_t)m * N + n];
+    __hip_atomic_fetch_add(out + n, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+static __global__ void k_zero_f32(float* __restrict__ p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
 }
 
 // Adam (Kingma & Ba, 2015) on the FP32 master weights; writes the BF16 copy.

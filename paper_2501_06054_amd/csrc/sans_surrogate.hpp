@@ -30,6 +30,10 @@ constexpr int kSteps = kHid / 32;   // 8 K-steps per hidden layer
 constexpr int64_t kPack0 = (int64_t)kTiles * 64;
 constexpr int64_t kPackL = (int64_t)kTiles * kSteps * 64;
 constexpr int64_t kPackTotal = kPack0 + 3 * kPackL;
+// The flat BF16 parameters as the tracer holds them: padded with zeros to a
+// multiple of 8 elements, so that the 8-byte loads of the last parameters
+// (b4 is element 199,936) lie wholly inside the buffer resource.
+constexpr int64_t kWeightsPadded = (mlp::kParams + 7) / 8 * 8;
 
 __host__ __device__ constexpr int perm_k(int g, int j) { return j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4); }
 
@@ -47,7 +51,8 @@ static __global__ void k_pack_surrogate(const __bf16* __restrict__ w, bf16x8* __
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int k = perm_k(g, j);
-            v[j] = k < kIn ? w[mlp::offW(0) + (int64_t)k * kHid + 16 * t + r] : (__bf16)0.0f;
+            // K rows 0..7: W0 for the hi parts of the inputs, 8..15: W0 again for the lo parts
+            v[j] = k < 2 * kIn ? w[mlp::offW(0) + (int64_t)(k % kIn) * kHid + 16 * t + r] : (__bf16)0.0f;
         }
     } else {
         const int64_t rem = id - kPack0;
@@ -111,12 +116,14 @@ __device__ __forceinline__ float forward16(__amdgpu_buffer_rsrc_t rp, __amdgpu_b
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
     const int loff = 16 * lane;
-    // input operand: features perm_k(g, j) of sample 16c + r (zero beyond 8)
+    // input operand: feature perm_k(g, j) of sample 16c + r: hi parts of the
+    // 8 inputs, then their lo parts, then zeros
     bf16x8 b0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int k = perm_k(g, j);
-        b0[j] = k < kIn ? (__bf16)xs[(16 * c + r) * kIn + k] : (__bf16)0.0f;
+        const float xv = k < 2 * kIn ? xs[(16 * c + r) * kIn + (k % kIn)] : 0.0f;
+        b0[j] = k < kIn ? mlp::bf16_hi(xv) : k < 2 * kIn ? mlp::bf16_lo(xv) : (__bf16)0.0f;
     }
     bf16x8 act[kSteps];
     // layer 0

@@ -278,6 +278,20 @@ def sans_f32_to_bf16(x, y, stream=None) -> None:
                                  _stream(stream)), "sans_f32_to_bf16")
 
 
+def sans_pq_dataset(kind: str, x, out, quad_n: int = 76, stream=None) -> None:
+    """Exact training targets ln(<V^2 P>/<V^2>) for surrogate inputs x [n][8]."""
+    _check(lib.sans_pq_dataset(KIND[kind], _dev(x, torch.float32, "x"), x.shape[0],
+                               _dev(out, torch.float32, "out"), quad_n, _stream(stream)),
+           "sans_pq_dataset")
+
+
+def sans_model_attach_surrogate(h, w_bf16, lo, hi) -> None:
+    lo4 = (C.c_float * 4)(*lo)
+    hi4 = (C.c_float * 4)(*hi)
+    _check(lib.sans_model_attach_surrogate(h, _dev(w_bf16, torch.bfloat16, "w_bf16"), lo4, hi4),
+           "sans_model_attach_surrogate")
+
+
 def sans_abi_params_size() -> int:
     return int(lib.sans_abi_params_size())
 

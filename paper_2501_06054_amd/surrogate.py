@@ -8,7 +8,10 @@ device buffers and shuffles the dataset once per epoch.
 """
 from __future__ import annotations
 
+import argparse
+import json
 import math
+import os
 import time
 
 import numpy as np
@@ -18,6 +21,15 @@ from . import sans
 from . import workloads as W
 
 KIND = {"parallelepiped": sans.KIND["parallelepiped"], "spheroid": sans.KIND["ellipsoid"]}
+DATA_KIND = {"parallelepiped": "parallelepiped", "spheroid": "ellipsoid"}
+
+#: Where the trained networks are kept (BF16 weights, FP32 master copy and
+#: the input box, safetensors).
+WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+
+
+def weights_path(model: str) -> str:
+    return os.path.join(WEIGHTS_DIR, f"surrogate_{model}.safetensors")
 
 
 def normalise(x: np.ndarray | torch.Tensor, lo, hi):
@@ -48,18 +60,15 @@ def init_params(seed: int) -> np.ndarray:
 
 
 def make_dataset(model: str, n: int, seed: int, quad_n: int = 76):
-    """(u, t) on the device: normalised inputs and exact targets."""
+    """(u, t) on the device: normalised inputs and exact targets
+    t = ln(<F^2>(q)/<F^2>(0)) - ln P_ref(q) (the network's residual)."""
     x = torch.from_numpy(W.surrogate_inputs(model, n, seed)).cuda()
     t = torch.empty(n, dtype=torch.float32, device="cuda")
     chunk = 1 << 20
     for i in range(0, n, chunk):
         xi = x[i:i + chunk].contiguous()
         ti = torch.empty(xi.shape[0], dtype=torch.float32, device="cuda")
-        rc = sans.lib.sans_pq_dataset(KIND[model], sans.C.c_void_p(xi.data_ptr()), xi.shape[0],
-                                      sans.C.c_void_p(ti.data_ptr()), quad_n,
-                                      sans.C.c_void_p(torch.cuda.current_stream().cuda_stream))
-        if rc != 0:
-            raise sans.SansError(rc, "sans_pq_dataset", sans.lib.sans_last_error().decode())
+        sans.sans_pq_dataset(DATA_KIND[model], xi, ti, quad_n)
         t[i:i + chunk] = ti
     lo, hi = W.SURROGATE_BOX[model]
     return normalise(x, lo, hi).contiguous(), t
@@ -133,8 +142,73 @@ class Surrogate:
         return hist
 
     def attach(self, model_handle) -> None:
-        lo = (sans.C.c_float * 4)(*self.lo)
-        hi = (sans.C.c_float * 4)(*self.hi)
-        rc = sans.lib.sans_model_attach_surrogate(model_handle, sans.C.c_void_p(self.wb.data_ptr()), lo, hi)
-        if rc != 0:
-            raise sans.SansError(rc, "sans_model_attach_surrogate", sans.lib.sans_last_error().decode())
+        sans.sans_model_attach_surrogate(model_handle, self.wb, self.lo, self.hi)
+
+    def save(self, path: str, meta: dict | None = None) -> None:
+        from safetensors.torch import save_file
+        box = torch.tensor([self.lo, self.hi], dtype=torch.float64)
+        md = {"model": self.model}
+        if meta:
+            md["train"] = json.dumps(meta)
+        save_file({"w_bf16": self.wb.cpu(), "w_fp32": self.w32.cpu(), "box": box}, path, metadata=md)
+
+    @classmethod
+    def load(cls, model: str, path: str | None = None) -> "Surrogate":
+        """A trained network (weights and input box) from its safetensors file."""
+        from safetensors.torch import load_file
+        t = load_file(path or weights_path(model))
+        sg = cls(model)
+        sg.w32.copy_(t["w_fp32"].cuda())
+        sg.wb.copy_(t["w_bf16"].cuda())
+        box = t["box"].numpy()
+        sg.lo, sg.hi = tuple(float(v) for v in box[0]), tuple(float(v) for v in box[1])
+        return sg
+
+    def evaluate(self, u: torch.Tensor, t: torch.Tensor) -> dict:
+        """Error of the network against targets ln P: on ln P and on P."""
+        d = (self.predict(u) - t).double()
+        rel = torch.expm1(d.abs())
+        return {"n": int(u.shape[0]), "lnp_rms": float(d.pow(2).mean().sqrt()),
+                "lnp_max": float(d.abs().max()), "p_rel_mean": float(rel.mean()),
+                "p_rel_p99": float(torch.quantile(rel[:1 << 20].float(), 0.99)),
+                "p_rel_max": float(rel.max())}
+
+
+def main(argv=None):
+    """Train one surrogate on the GPU (own kernels end to end) and write it."""
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--model", choices=sorted(KIND), required=True)
+    ap.add_argument("--n", type=float, default=1e7, help="training samples")
+    ap.add_argument("--n-val", type=float, default=2e5, help="held-out samples")
+    ap.add_argument("--epochs", type=float, default=120)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    n, nv = int(a.n), int(a.n_val)
+    t0 = time.perf_counter()
+    u, t = make_dataset(a.model, n, seed=1000 + a.seed)
+    uv, tv = make_dataset(a.model, nv, seed=2000 + a.seed)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    steps = int(a.epochs * n / a.batch)
+    sg = Surrogate(a.model, seed=a.seed)
+    t0 = time.perf_counter()
+    hist = sg.train(u, t, steps=steps, batch=a.batch, lr=a.lr, seed=a.seed,
+                    log_every=max(1, steps // 20))
+    t_train = time.perf_counter() - t0
+    for k, loss, el in hist:
+        print(f"step {k:7d}  mse(ln P) {loss:.3e}  {el:7.1f} s", flush=True)
+    ev = sg.evaluate(uv, tv)
+    meta = {"n": n, "epochs": a.epochs, "batch": a.batch, "lr": a.lr, "seed": a.seed,
+            "steps": steps, "dataset_s": round(t_data, 2), "train_s": round(t_train, 2),
+            "validation": ev}
+    out = a.out or weights_path(a.model)
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+    sg.save(out, meta)
+    print(json.dumps(dict(meta, model=a.model, out=out)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

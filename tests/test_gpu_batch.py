@@ -47,7 +47,11 @@ def test_batch_equals_plain(S):
 
 
 def test_batch_matches_oracle_subset(S):
-    exps = _small_batch()
+    # Pixel parity is judged where pixels hold many neutrons (about 100 per
+    # pixel of the 128x128 detector at 1e6 neutrons); with a handful per
+    # pixel a pixel can be one neutron whose amplitude sits near a zero of
+    # F, which only the per-neutron bar (with its w_max term) governs.
+    exps = _small_batch(n_lo=6e5, n_hi=2e6)
     got = _run_batch(S, exps)
     for e in (0, 1, 2, 3, 5, 8, 13, 21):
         x = exps[e]
@@ -85,7 +89,11 @@ def test_batch_zero_and_ragged_counts(S):
         x = exps[e]
         ref = oracle.trace(x["params"], x["n"], x["seed"], exp_id=e, nthreads=NTHREADS)
         assert np.array_equal(got[e] != 0, ref != 0)
-        assert abs(got[e].sum() - ref.sum()) <= 1e-6 * abs(ref.sum())
+        if x["n"] == 1:
+            # one neutron: the per-neutron bar, |dw| <= 1e-5 w_max + 1e-4 |w|, w_max = |w|
+            assert abs(got[e].sum() - ref.sum()) <= 1.1e-4 * abs(ref.sum())
+        else:
+            assert abs(got[e].sum() - ref.sum()) <= 1e-6 * abs(ref.sum())
 
 
 def test_batch_tuning_cache(S, tmp_path):
