@@ -31,42 +31,55 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks and unit counts
 PEAK_FP32_TFLOPS = 157.3
 CUS, CLOCK_GHZ = 256, 2.4
-# VALU issue ceiling: 4 SIMDs of 16 lanes per CU, one lane-operation per lane
-# per clock (a wave64 instruction every 4 clocks per SIMD): 64 lane-slots per
-# clock per CU.  FP64 add/mul/fma issue at this rate on MI355X, as unpacked
-# FP32 does.
-PEAK_VALU_TSLOTS = CUS * CLOCK_GHZ * 1e9 * 64 / 1e12
+# The VALU ceiling in FP32-FMA lane slots: 157.3 TFLOP/s = 256 CUs x 2.4 GHz
+# x 128 FMA lanes per clock (two wave64 FP32 FMAs per clock per CU).
+PEAK_VALU_TSLOTS = PEAK_FP32_TFLOPS / 2.0
 
-# Algorithmic work per neutron, counted from the method's steps (the
-# derivation is tabulated in the design notes).  Counting rules, per lane:
-#   slots: 1 per FP64/FP32/integer add, mul, fma, min/max, compare/select or
-#          conversion; 4 per quarter-rate op (32x32->64 integer multiply, FP32
-#          reciprocal/sqrt/exp/log); 8 per FP64 reciprocal, divide or sqrt;
-#          where a function has a short series below a threshold, the cheaper
-#          (series) cost is counted, so the totals are lower bounds.
-#   fp32:  FP32 flops of the weight (add/mul 1, fma 2, reciprocal/sqrt 1).
+# Issue cost of each operation class in FP32-FMA slots, from the rates
+# measured on MI355X by sans_debug_valu_rates (bench.py --workload
+# valu_rates; wave64 instructions per clock per CU: FP32 FMA 1.49, 32-bit
+# integer 1.54, 32x32->64 multiply with an xor 0.86, FP64 FMA 0.79, FP32
+# reciprocal 0.45, FP64 reciprocal 0.24).  A GPU test keeps the measured
+# costs within 30 % of these.
+SLOT_COST = {"fp32": 1.0, "int32": 1.0, "mul64": 2.5, "fp64": 1.9, "trans32": 3.3, "trans64": 6.3}
+
+# Algorithmic work per neutron, counted from the method's steps (tabulated in
+# the design notes): operations per lane by class -- fp32 and fp64 add, mul,
+# fma, min/max, compare or conversion; int32 add, xor, logic or select;
+# mul64 a 32x32->64 multiply; trans32 an FP32 reciprocal/sqrt/exp/log; trans64
+# the FP64 reciprocal or rsq estimate (the Newton steps that refine it are
+# fp64 ops).  Where a function has a short series below a threshold, the
+# cheaper (series) form is counted, so the totals are lower bounds.  The last
+# column is the FP32 flops of the weight (fma 2).
+#           step               fp32 int32 mul64 fp64 trans32 trans64 | fp32 flops
 STEP = {
-    # step                slots  fp32
-    "philox_block":      (100,   0),   # 10 rounds x (2 multiplies x 4 + 2 xor3); key schedule is scalar
-    "uniform":           (2,     0),   # u32 -> f64, fma
-    "source_slit":       (39,    0),   # A3: points, direction (sqrt, rcp), lambda, k = 2 pi/lambda
-    "slab":              (51,    0),   # A4: 3 axes x (rcp 8, 2 fma-pairs, min/max 4), length
-    "scatter_point":     (4,     0),   # A5
-    "cone_q":            (85,    0),   # A6: t, sqrt, sincospi(psi), Duff basis, k_f, |Q|
-    "qvec":              (6,     0),   # Q vector (anisotropic models)
-    "size_draw":         (10,    0),   # A7: FP64 table lerp
-    "orient_angle":      (31,    0),   # A8 per Gaussian angle: lerp, small-angle sincos, rotation
-    "project_c":         (5,     0),   # Q . C
-    "project_abc":       (27,    0),   # Q . A, Q . B, Q . C
-    "sphere_F":          (13,   21),   # A9: 3 j1(x)/x (series) and volume
-    "core_shell_F":      (32,   44),
-    "cylinder_F":        (32,   39),   # sinc (series), 2 J1(x)/x (series), Q_AB
-    "ellipsoid_F":       (26,   25),
-    "py_sq":             (17,   25),   # A10: series in x^2, 1/(1 + 24 phi G/x)
-    "weight":            (5,     3),   # A11
-    "detector":          (26,    0),   # A12: plane crossing (divide), pixel
-    "tally":             (2,     0),   # A13: address; the atomic is a memory op
+    "philox_block":  ((0,  40, 20,  0, 0, 0), 0),   # 10 rounds: 2 multiplies, 4 xor
+    "uniform":       ((0,   0,  0,  2, 0, 0), 0),   # u32 -> f64, fma
+    "source_slit":   ((0,   0,  0, 30, 0, 3), 0),   # A3: points, |d| (sqrt), 1/|d|, lambda, 2 pi/lambda
+    "slab":          ((0,   2,  0, 38, 0, 3), 0),   # A4: 3 axes x (1/k_c, 2 planes, min/max), chord
+    "scatter_point": ((0,   0,  0,  4, 0, 0), 0),   # A5
+    "cone_q":        ((0,   8,  0, 69, 0, 3), 0),   # A6: t, sqrt, sincospi(psi), Duff basis, k_f, |Q|
+    "qvec":          ((0,   0,  0,  6, 0, 0), 0),   # Q vector (anisotropic models)
+    "size_draw":     ((0,   2,  0, 10, 0, 0), 0),   # A7: FP64 table lerp
+    "orient_angle":  ((0,   2,  0, 31, 0, 0), 0),   # A8 per Gaussian angle: lerp, Taylor sincos, rotation
+    "project_c":     ((0,   0,  0,  5, 0, 0), 0),   # Q . C
+    "project_abc":   ((0,   0,  0, 27, 0, 0), 0),   # Q . A, Q . B, Q . C
+    "sphere_F":      ((15,  0,  0,  4, 0, 0), 21),  # A9: phase, 3 j1(x)/x series, volume
+    "core_shell_F":  ((29,  0,  0, 10, 0, 0), 44),
+    "cylinder_F":    ((24,  0,  0, 13, 0, 1), 39),  # Q_AB (sqrt), sinc and 2 J1(x)/x series
+    "ellipsoid_F":   ((15,  0,  0, 15, 0, 1), 25),  # |(aQ_A, bQ_B, cQ_C)| (sqrt), series
+    "py_sq":         ((15,  0,  0,  0, 1, 0), 25),  # A10: series in x^2, 1/(1 + 24 phi G/x)
+    "weight":        ((3,   0,  0,  2, 0, 0), 3),   # A11
+    "detector":      ((0,   5,  0, 23, 0, 1), 0),   # A12: plane crossing (quotient), pixel
+    "tally":         ((0,   2,  0,  0, 0, 0), 0),   # A13: address; the add itself is a memory op
 }
+_CLASSES = ("fp32", "int32", "mul64", "fp64", "trans32", "trans64")
+
+
+def step_slots(ops) -> float:
+    return sum(n * SLOT_COST[c] for n, c in zip(ops, _CLASSES))
+
+
 COMMON = ["source_slit", "slab", "scatter_point", "cone_q", "weight", "detector", "tally"]
 PATHS = {
     "tiny_sphere": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["sphere_F"],
@@ -77,26 +90,30 @@ PATHS = {
     "oriented_ellipsoid": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
                           + ["qvec"] + ["orient_angle"] * 3 + ["project_abc", "ellipsoid_F"],
 }
-# Exact-average paths: per quadrature node (76 x 76 = 5776 nodes per neutron)
-# parallelepiped: 2 in-plane projections (2), three sinc (series, 7 each),
-# product and accumulation (5); spheroid: sin(theta) (sqrt, 6), projections (2),
-# argument (3 mul + 2 fma + sqrt = 9), 3 j1(x)/x (series, 9), volume (4),
-# accumulation (2).  FP32 flops per node: 2 + 3 x 11 + 5 = 40 and 6 + 2 + 11 +
-# 17 + 4 + 3 = 43.
-QUAD_NODE = {"quad_parallelepiped": (28, 40), "quad_spheroid": (32, 43)}
+# Exact-average paths, per quadrature node (76 x 76 = 5776 nodes per neutron),
+# all FP32:
+#   parallelepiped (amplitude = product of one factor per axis; the C factor
+#   depends on mu only and is taken once per mu node): 2 arguments, two sinc
+#   series (5 each), product, square, weighted sum: 15 ops, 24 flops; per mu
+#   node the C sinc and its weight: 12 ops, 20 flops;
+#   spheroid (mu x size nodes): q mu, q st, 3 mul, 2 fma, sqrt (trans32), the
+#   3 j1(x)/x series (9), square and weighted sum: 18 ops + 1 trans32, 35 flops.
+QUAD_NODE = {"quad_parallelepiped": ((15, 0, 0, 0, 0, 0), 24), "quad_spheroid": ((18, 0, 0, 0, 1, 0), 35)}
+QUAD_MU = {"quad_parallelepiped": ((12, 0, 0, 0, 0, 0), 20), "quad_spheroid": ((0, 0, 0, 0, 0, 0), 0)}
 QUAD_NODES = 76 * 76
 QUAD_BASE = COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["qvec"]
 
 
 def algo_per_neutron(workload: str):
-    """(VALU slots, FP32 flops) per neutron of a workload, or None."""
+    """(FP32-FMA slots, FP32 flops) per neutron of a workload, or None."""
     if workload in PATHS:
         steps = PATHS[workload]
-        return sum(STEP[s][0] for s in steps), sum(STEP[s][1] for s in steps)
+        return (round(sum(step_slots(STEP[x][0]) for x in steps), 1), sum(STEP[x][1] for x in steps))
     if workload in QUAD_NODE:
-        base = sum(STEP[s][0] for s in QUAD_BASE)
-        slots, flops = QUAD_NODE[workload]
-        return base + QUAD_NODES * slots, STEP["weight"][1] + QUAD_NODES * flops
+        base = sum(step_slots(STEP[x][0]) for x in QUAD_BASE)
+        (nops, nflops), (mops, mflops) = QUAD_NODE[workload], QUAD_MU[workload]
+        return (round(base + QUAD_NODES * step_slots(nops) + 76 * step_slots(mops), 1),
+                STEP["weight"][1] + QUAD_NODES * nflops + 76 * mflops)
     return None
 
 
@@ -108,6 +125,8 @@ def parse():
     ap.add_argument("--workload", default="coreshell_py")
     ap.add_argument("--n", type=float, default=None, help="neutrons per step (default: workload's)")
     ap.add_argument("--tally", default="auto", choices=["auto", "global", "lds", "xcd", "binned"])
+    ap.add_argument("--sweep", action="store_true",
+                    help="time one trace call per neutron count 1e5 .. 1e10 instead")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample (0 = skip)")
     return ap.parse_args()
@@ -125,9 +144,27 @@ def cpu_baseline(params, seed, target_s):
     t0 = time.perf_counter()
     oracle.trace(params, n_s, seed, nthreads=threads)
     dt = time.perf_counter() - t0
+    # one thread, the paper's single-core reference scheme (about 3 s of work)
+    n1 = int(max(20_000, min(rate / threads * 3.0, 5e8)))
+    t0 = time.perf_counter()
+    oracle.trace(params, n1, seed, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return dict(value=n_s / dt, unit="neutrons/s", cores=threads, kind="oracle",
                 sample=f"first {n_s} neutrons of the same workload and seed "
-                       f"(FP64 C oracle, {threads} threads, {dt:.1f} s)")
+                       f"(FP64 C oracle, {threads} threads, {dt:.1f} s)",
+                single_thread=dict(value=n1 / dt1, sample=f"first {n1} neutrons, 1 thread, {dt1:.1f} s"))
+
+
+def bench_valu_rates(a):
+    """Issue rates of the VALU operation classes the slot costs rest on."""
+    import torch
+    from paper_2501_06054_amd import sans
+    torch.cuda.set_device(0)
+    rates = sans.sans_debug_valu_rates()
+    return {"metric": "VALU issue rate", "unit": "wave64 instructions per clock per CU",
+            "rates": {k: round(v, 3) for k, v in rates.items()},
+            "slot_cost_vs_fp32_fma": {k: round(rates["fp32 fma"] / v, 2) for k, v in rates.items()},
+            "note": "the mul 32x32->64 class is a multiply plus an xor (two instructions)"}
 
 
 def bench_copy(a):
@@ -168,7 +205,9 @@ def bench_batch(a):
     total = float(sum(ns))
     torch.cuda.set_device(0)
     out = torch.empty((len(exps), 128, 128), dtype=torch.float64, device="cuda")
-    tune = os.path.join(ROOT, "profiles", "batch_tuning.json")
+    # the autotuner's cache (one entry per batch shape) lives outside the tree
+    import tempfile
+    tune = os.path.join(tempfile.gettempdir(), "sans_batch_tuning.json")
     sans.sans_trace_batch(plist, ns, seeds, out, tune_cache=tune)   # tunes once (cached file)
     for _ in range(a.warmup):
         sans.sans_trace_batch(plist, ns, seeds, out, tune_cache=tune)
@@ -206,6 +245,29 @@ def bench_batch(a):
                            "sample": "first 256 experiments, one sans_trace_ex each"},
         "batched_over_plain": round(value / plain_rate, 3),
     }
+
+
+def sweep(m, p, seed, workload):
+    """Wall time of one trace call (detector cleared, events on the stream)
+    for N = 1e5 .. 1e10: the shape of the paper's time-versus-N curves."""
+    import torch
+    det = m.detector()
+    rows = []
+    for e in range(5, 11):
+        n = 10 ** e
+        m.trace(min(n, 10 ** 7), seed, det=det)          # warm
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        m.trace(n, seed, det=det)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        rows.append({"n": n, "wall_ms": round(wall * 1e3, 4), "gpu_ms": round(e0.elapsed_time(e1), 4),
+                     "neutrons_per_s": round(n / wall, 1)})
+    return {"metric": "trace time versus neutron count", "workload": workload,
+            "detector": f"{p['nx']}x{p['ny']}", "rows": rows}
 
 
 def kernel_source_hash() -> str:
@@ -254,6 +316,9 @@ def main():
     if a.workload == "copy":
         print(json.dumps(bench_copy(a)), flush=True)
         return
+    if a.workload == "valu_rates":
+        print(json.dumps(bench_valu_rates(a)), flush=True)
+        return
 
     import torch
     from paper_2501_06054_amd import sans, workloads as W
@@ -264,7 +329,15 @@ def main():
     seed = wl["seed"]
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
     m = sans.Model(p, tally=a.tally)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t_setup) * 1e3
+    if a.sweep:
+        print(json.dumps(sweep(m, p, seed, a.workload)), flush=True)
+        m.close()
+        return
     if p["mode"] == "surrogate":
         from paper_2501_06054_amd import surrogate as SG
         model = "parallelepiped" if p["kind"] == "parallelepiped" else "spheroid"
@@ -303,7 +376,8 @@ def main():
         ach = slots * kernel_rate / 1e12
         traffic = measured_traffic(a.workload, "trace_call", n)
         roofline = dict(bound="alu", achieved=round(ach, 3), peak=round(PEAK_VALU_TSLOTS, 3),
-                        unit="Tslot/s (VALU lane-op issue)", frac=round(ach / PEAK_VALU_TSLOTS, 4),
+                        unit="T FP32-FMA lane slots/s (VALU issue, 157.3 TFLOP/s / 2)",
+                        frac=round(ach / PEAK_VALU_TSLOTS, 4),
                         traffic=(None if traffic is None else round(traffic[0] + traffic[1])),
                         timed="one sans_trace call: all of its kernels (trace kernel launches and "
                               "tally reduction), HIP events on its stream",
@@ -329,6 +403,7 @@ def main():
                    "model": p["kind"], "mode": p["mode"], "detector": f"{p['nx']}x{p['ny']}",
                    "tally": a.tally, "parallelism": "none (1 GPU)"},
         "detector_total": total,
+        "setup_ms": round(setup_ms, 3),
         "roofline": roofline,
         "fp32_valu": fp32,
     }

@@ -193,6 +193,15 @@ int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uin
 int sans_debug_trace(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed,
                      uint32_t exp_id, int32_t* pixel, float* w, float* q, void* stream);
 
+/* Measured VALU issue rates (synchronous; about 10 ms): rates (host double
+ * [6]) receives wave64 instructions per clock per compute unit, at the
+ * device's nominal clock, of dependency-free streams of (0) 32-bit integer
+ * xor/add, (1) a 32x32->64 multiply followed by an xor (two instructions),
+ * (2) FP32 FMA, (3) FP64 FMA, (4) FP32 reciprocal, (5) FP64 reciprocal.
+ * They weigh the algorithmic operation counts of the throughput report
+ * (one FP32 FMA per lane per clock per SIMD of 16 lanes = 1.0). */
+int sans_debug_valu_rates(double* rates, void* stream);
+
 /* Raw Philox4x32-10 words (Salmon et al., SC'11) of the neutron streams:
  * out (device uint32 [n][n_blocks][4]) receives block b of neutron first+j,
  * counter (lo i, hi i, b, exp_id), key (lo seed, hi seed). */
@@ -256,7 +265,8 @@ int sans_model_constants(sans_model_t m, double* out3);
  * (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; operands are rounded to
  * BF16 (round to nearest even) when they are loaded, except the 8 inputs of
  * the first layer, which enter as two BF16 parts hi = bf16(x) and
- * lo = bf16(x - hi), both multiplied by W0 (16 bits of input precision).
+ * lo = bf16(x - hi), both multiplied by W0 (16 bits of input precision), and
+ * the last hidden activations, which enter the output layer in FP32.
  * ------------------------------------------------------------------------- */
 
 /* Number of parameters (199,937). */

@@ -862,7 +862,10 @@ int orc_trace(const orc_params* p, uint64_t first, uint64_t n, uint64_t seed, ui
  * b1 W2 b2 W3 b3 W4[256] b4 (W stored [in][out]).  FP64 arithmetic; with
  * round_bf16 set, every operand of a matrix product is first rounded to
  * FP32 and then to BF16 (round to nearest even), the operand precision the
- * device uses, so that the comparison isolates the accumulation.           */
+ * device uses, so that the comparison isolates the accumulation; the two
+ * exceptions follow the network's definition: each input enters as the sum
+ * of its two BF16 parts, and the output layer takes the last activations
+ * unrounded.                                                               */
 #define ORC_NIN 8
 #define ORC_NH 256
 #define ORC_NP 199937
@@ -926,8 +929,9 @@ void orc_mlp_forward(const double* w, const double* x, int32_t n, double* y, int
             }
             memcpy(a, b, sizeof(double) * ORC_NH);
         }
+        /* output layer: the last activations enter unrounded */
         double s = 0.0;
-        for (int k = 0; k < ORC_NH; ++k) s += op(a[k], round_bf16) * op(w[ORC_OFFW4 + k], round_bf16);
+        for (int k = 0; k < ORC_NH; ++k) s += a[k] * op(w[ORC_OFFW4 + k], round_bf16);
         y[i] = s + op(w[ORC_OFFW4 + ORC_NH], round_bf16);
     }
     free(a);

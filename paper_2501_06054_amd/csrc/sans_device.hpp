@@ -53,6 +53,9 @@ template <int M> struct CosD { static constexpr double v = cos_coef(M); };
 
 constexpr int kPySeriesTerms = 12;
 constexpr int kMaxQuad = 256;
+// orientation node arrays of the exact average: mu, w_mu, cos beta, sin beta,
+// w_beta, sqrt(1 - mu^2)
+constexpr int kQuadArrays = 6;
 
 // ---------------------------------------------------------------- arguments
 // Everything a trace kernel needs, passed by value as the kernel argument.
@@ -473,7 +476,10 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
 
 // ---------------------------------------------------------------- exact average
 // <F^2>(q) over the Schulz size nodes and (isotropic) the orientation nodes
-// held in LDS: lq = mu[n] wmu[n] cb[n] sb[n] wb[n] y[ny] wy[ny].
+// held in LDS: lq = mu[n] wmu[n] cb[n] sb[n] wb[n] st[n] y[ny] wy[ny], with
+// st = sqrt(1 - mu^2).  The parallelepiped's amplitude is a product of one
+// factor per axis, so its C factor (which depends on mu only) leaves the
+// inner beta sum: <F^2> = sum_i w_i F_C(mu_i)^2 sum_l w_l F_A^2 F_B^2.
 template <int KIND>
 __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* lq, float q,
                                               const float qv[3])
@@ -484,8 +490,9 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* l
     const float* cb = lq + 2 * n;
     const float* sb = lq + 3 * n;
     const float* wb = lq + 4 * n;
-    const float* ys = lq + 5 * n;
-    const float* wy = lq + 5 * n + ny;
+    const float* stt = lq + 5 * n;
+    const float* ys = lq + kQuadArrays * n;
+    const float* wy = lq + kQuadArrays * n + ny;
     float qa0 = 0.0f, qb0 = 0.0f, qc0 = 0.0f;
     if (a.quad_dims == 0 && KIND >= kCylinder) {
         qa0 = qv[0] * a.fA[0] + qv[1] * a.fA[1] + qv[2] * a.fA[2];
@@ -504,16 +511,27 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* l
             avg = f * f;
         } else if (a.quad_dims == 1) {
             for (int i = 0; i < n; ++i) {
-                const float m = mu[i];
-                const float st = sqrtf(fmaxf(1.0f - m * m, 0.0f));
-                const float f = amplitude_f<KIND>(a, s, q, q * st, 0.0f, q * m);
+                const float f = amplitude_f<KIND>(a, s, q, q * stt[i], 0.0f, q * mu[i]);
                 avg = __builtin_fmaf(wmu[i], f * f, avg);
             }
+        } else if constexpr (KIND == kParallelepiped) {
+            const float f0 = a.contrast * s[0] * s[1] * s[2];
+            const float ha = 0.5f * q * s[0], hb = 0.5f * q * s[1], hc = 0.5f * q * s[2];
+            for (int i = 0; i < n; ++i) {
+                const float fc = sinc_f(hc * mu[i]);
+                const float xa = ha * stt[i], xb = hb * stt[i];
+                float inner = 0.0f;
+                for (int l = 0; l < n; ++l) {
+                    const float g = sinc_f(xa * cb[l]) * sinc_f(xb * sb[l]);
+                    inner = __builtin_fmaf(wb[l], g * g, inner);
+                }
+                avg = __builtin_fmaf(wmu[i] * fc * fc, inner, avg);
+            }
+            avg *= f0 * f0;
         } else {
             for (int i = 0; i < n; ++i) {
-                const float m = mu[i];
-                const float qst = q * sqrtf(fmaxf(1.0f - m * m, 0.0f));
-                const float qc = q * m;
+                const float qst = q * stt[i];
+                const float qc = q * mu[i];
                 float inner = 0.0f;
                 for (int l = 0; l < n; ++l) {
                     const float f = amplitude_f<KIND>(a, s, q, qst * cb[l], qst * sb[l], qc);

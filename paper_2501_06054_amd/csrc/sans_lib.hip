@@ -209,7 +209,12 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const TraceArgs a, LdsLayou
 
 // Binned tally, pass 2: workgroup (t, s) sums the segments of waves
 // [s W/S, (s+1) W/S) of tile t in an LDS histogram of the tile (each of its
-// waves takes every 16th segment) and adds it to its own partial slot.
+// waves takes every 16th segment) and adds it to its own partial slot.  A
+// wave first reads the counts of up to 64 of its segments at once (one per
+// lane), then streams each segment with kAccUnroll loads in flight per lane
+// before their LDS atomics.
+constexpr int kAccUnroll = 8;
+
 __global__ __launch_bounds__(kHistBlock) void k_bin_accumulate(const uint2* buckets, const unsigned* seg_count,
                                                                unsigned capw, unsigned nwaves, int tile_pixels,
                                                                int slices, double* partial)
@@ -221,14 +226,28 @@ __global__ __launch_bounds__(kHistBlock) void k_bin_accumulate(const uint2* buck
     const unsigned w0 = (unsigned)((uint64_t)nwaves * sl / slices);
     const unsigned w1 = (unsigned)((uint64_t)nwaves * (sl + 1) / slices);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (unsigned w = w0 + wave; w < w1; w += kHistBlock / 64) {
-        const size_t seg = (size_t)t * nwaves + w;
-        const unsigned cnt = seg_count[seg];
-        const uint2* b = buckets + seg * capw;
-        for (unsigned i = lane; i < cnt; i += 64) {
-            const uint2 e = b[i];
-            __hip_atomic_fetch_add(hist + e.x, (double)__uint_as_float(e.y), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+    constexpr unsigned kWaves = kHistBlock / 64;
+    for (unsigned g0 = w0 + wave; g0 < w1; g0 += 64 * kWaves) {
+        // lane k: count of segment g0 + k * kWaves
+        const unsigned wl = g0 + (unsigned)lane * kWaves;
+        const unsigned mycnt = wl < w1 ? seg_count[(size_t)t * nwaves + wl] : 0u;
+        const int nseg = (int)std::min<unsigned>(64u, (w1 - g0 + kWaves - 1) / kWaves);
+        for (int k = 0; k < nseg; ++k) {
+            const unsigned cnt = (unsigned)__builtin_amdgcn_readlane((int)mycnt, k);
+            const uint2* b = buckets + ((size_t)t * nwaves + g0 + (unsigned)k * kWaves) * capw;
+            for (unsigned i0 = 0; i0 < cnt; i0 += 64 * kAccUnroll) {
+                uint2 e[kAccUnroll];
+#pragma unroll
+                for (int u = 0; u < kAccUnroll; ++u) {
+                    const unsigned i = i0 + (unsigned)(u * 64 + lane);
+                    e[u] = i < cnt ? b[i] : make_uint2(0u, 0u);
+                }
+#pragma unroll
+                for (int u = 0; u < kAccUnroll; ++u)
+                    if (e[u].y != 0u)
+                        __hip_atomic_fetch_add(hist + e[u].x, (double)__uint_as_float(e[u].y), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
     }
     __syncthreads();
@@ -635,6 +654,45 @@ __global__ __launch_bounds__(kBlock) void k_pq_dataset(const TraceArgs a, const 
     out[idx] = (float)(log(num / den) + 2.0 * log1p(exp(2.0 * (double)xi[0]) * rg2 / 6.0));
 }
 
+// ------------------------------------------------------------------ VALU issue-rate probe
+// Eight independent dependency chains per lane of one operation class; the
+// issue cost of each class (relative to an FP32 FMA) weighs the algorithmic
+// operation counts of the trace kernels.
+constexpr int kProbeIter = 2048;
+constexpr int kProbeChains = 8;
+
+template <int OP>
+__global__ __launch_bounds__(256) void k_valu_probe(uint32_t* out, uint32_t seed)
+{
+    uint32_t u[kProbeChains];
+    double d[kProbeChains];
+    float f[kProbeChains];
+#pragma unroll
+    for (int j = 0; j < kProbeChains; ++j) {
+        u[j] = threadIdx.x * 2654435761u + (uint32_t)j * 77u + seed;
+        d[j] = 1.0 + 1e-3 * (double)threadIdx.x + j;
+        f[j] = 1.0f + 1e-3f * (float)threadIdx.x + (float)j;
+    }
+    for (int i = 0; i < kProbeIter; ++i) {
+#pragma unroll
+        for (int j = 0; j < kProbeChains; ++j) {
+            if constexpr (OP == 0) u[j] = (u[j] ^ (seed + (uint32_t)j)) + 0x9E3779B9u;        // 2 int32 ops
+            if constexpr (OP == 1) {                                                          // mul64 + xor
+                const uint64_t p = (uint64_t)0xD2511F53u * u[j];
+                u[j] = (uint32_t)p ^ (uint32_t)(p >> 32);
+            }
+            if constexpr (OP == 2) f[j] = __builtin_fmaf(f[j], 0.999f, 0.25f);
+            if constexpr (OP == 3) d[j] = __builtin_fma(d[j], 0.999, 0.25);
+            if constexpr (OP == 4) f[j] = __builtin_amdgcn_rcpf(f[j]);
+            if constexpr (OP == 5) d[j] = __builtin_amdgcn_rcp(d[j]);
+        }
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < kProbeChains; ++j) r ^= u[j] ^ __float_as_uint(f[j]) ^ (uint32_t)__double_as_longlong(d[j]);
+    out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = r;
+}
+
 // ------------------------------------------------------------------ dispatch tables
 using TraceFn = void (*)(const TraceArgs, LdsLayout, double*, double*, unsigned long long*, double*);
 using DebugFn = void (*)(const TraceArgs, LdsLayout, int32_t*, float*, float*);
@@ -1018,7 +1076,7 @@ int configure(sans_model_s* m, const sans_params* p)
         a.quad_n = n;
         a.quad_ny = ny;
         a.quad_dims = dims;
-        m->h_quad.assign(5 * n + 2 * ny, 0.0f);
+        m->h_quad.assign(kQuadArrays * n + 2 * ny, 0.0f);
         for (int i = 0; i < n; ++i) {
             const double mu = 0.5 * (gx[i] + 1.0);
             const double beta = 0.25 * 3.141592653589793 * (gx[i] + 1.0);
@@ -1027,10 +1085,11 @@ int configure(sans_model_s* m, const sans_params* p)
             m->h_quad[2 * n + i] = (float)std::cos(beta);
             m->h_quad[3 * n + i] = (float)std::sin(beta);
             m->h_quad[4 * n + i] = (float)(0.5 * gw[i]);
+            m->h_quad[5 * n + i] = (float)std::sqrt(1.0 - mu * mu);
         }
         for (int j = 0; j < ny; ++j) {
-            m->h_quad[5 * n + j] = (float)ys[j];
-            m->h_quad[5 * n + ny + j] = (float)wy[j];
+            m->h_quad[kQuadArrays * n + j] = (float)ys[j];
+            m->h_quad[kQuadArrays * n + ny + j] = (float)wy[j];
         }
         // <F^2> at q = 0 over the same size nodes: (drho V(y))^2 averaged
         {
@@ -1066,7 +1125,7 @@ LdsLayout layout(const sans_model_s* m, bool hist)
     l.tab_norm = off;
     if (a.tab_norm) off += a.M;
     l.quad = off;
-    l.quad_floats = (m->p.mode != SANS_MODE_MC) ? 5 * a.quad_n + 2 * a.quad_ny : 0;
+    l.quad_floats = (m->p.mode != SANS_MODE_MC) ? kQuadArrays * a.quad_n + 2 * a.quad_ny : 0;
     off += (l.quad_floats + 1) / 2;
     l.total = off;
     return l;
@@ -1445,6 +1504,45 @@ int sans_debug_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t n_bloc
     hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
                        (uint32_t)seed, (uint32_t)(seed >> 32), first, n, n_blocks, exp_id, out);
     HIP_TRY(hipGetLastError());
+    return SANS_OK;
+}
+
+int sans_debug_valu_rates(double* rates, void* stream)
+{
+    (void)hipGetLastError();  // a stale error of an earlier call is not ours
+    if (!rates) return fail(SANS_E_INVALID_ARG, "rates is NULL");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    const unsigned blocks = (unsigned)prop.multiProcessorCount * 16, threads = 256;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t* out = nullptr;
+    HIP_TRY(hipMalloc(&out, sizeof(uint32_t) * blocks * threads));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    using Probe = void (*)(uint32_t*, uint32_t);
+    const Probe probes[6] = {k_valu_probe<0>, k_valu_probe<1>, k_valu_probe<2>,
+                             k_valu_probe<3>, k_valu_probe<4>, k_valu_probe<5>};
+    const int per_step[6] = {2, 2, 1, 1, 1, 1};
+    for (int k = 0; k < 6 && e == hipSuccess; ++k) {
+        hipLaunchKernelGGL(probes[k], dim3(blocks), dim3(threads), 0, s, out, 3u);   // warm
+        hipEventRecord(e0, s);
+        hipLaunchKernelGGL(probes[k], dim3(blocks), dim3(threads), 0, s, out, 5u);
+        hipEventRecord(e1, s);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        const double waves = (double)blocks * threads / 64.0;
+        const double instr = waves * kProbeIter * kProbeChains * per_step[k];
+        rates[k] = instr / (ms * 1e-3) / (prop.clockRate * 1e3) / prop.multiProcessorCount;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    if (e != hipSuccess) return fail(SANS_E_HIP, std::string("valu probe: ") + hipGetErrorString(e));
     return SANS_OK;
 }
 

@@ -85,9 +85,12 @@ int sans_mlp_forward(const void* w_bf16, const float* x, int64_t n, float* y, vo
                                                                    w + offW(l), kHid, ws_z(W, n, l), kHid,
                                                                    w + offB(l), ws_h(W, n, l), s)))
             return rc;
-    // y = H3 W4 + b4
-    return gemm<false, false, float, __bf16, kEpiBias>(N, 1, kHid, ws_h(W, n, 3), kHid, w + kOffW4, 1, y,
-                                                        1, w + kOffB4, nullptr, s);
+    // y = H3 W4 + b4 (FP32 activations)
+    hipLaunchKernelGGL(k_output, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, ws_h(W, n, 3), w + kOffW4,
+                       w + kOffB4, N, y);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return mfail(SANS_E_HIP, std::string("output layer: ") + hipGetErrorString(e));
+    return SANS_OK;
 }
 
 int sans_mlp_backward(const void* w_bf16, const float* x, const float* dy, int64_t n, float* dw, void* ws,

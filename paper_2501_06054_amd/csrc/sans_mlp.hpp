@@ -8,7 +8,9 @@
 // W_l is stored [in][out] row-major.  Matrix products use
 // v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation.  The inputs of
 // the first layer enter as two BF16 parts, hi = bf16(x) and lo = bf16(x -
-// hi), both multiplied by W0 (16 bits of input precision instead of 8).
+// hi), both multiplied by W0 (16 bits of input precision instead of 8); the
+// output layer takes the last hidden activations in FP32 (a dot product
+// with the BF16 W4, FP32 arithmetic).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -165,6 +167,24 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const TA* __r
                     C[o] = v * silu_grad(aux[o]);
                 }
             }
+}
+
+// Output layer: y[m] = sum_k H[m][k] W4[k] + b4 with FP32 activations; one
+// wave per row, four features per lane.
+static __global__ void k_output(const float* __restrict__ H, const __bf16* __restrict__ w4,
+                                const __bf16* __restrict__ b4, int M, float* __restrict__ y)
+{
+    const int lane = threadIdx.x & 63;
+    const int m = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (m >= M) return;
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kHid / 64; ++i) {
+        const int k = i * 64 + lane;
+        s = __builtin_fmaf(H[(int64_t)m * kHid + k], (float)w4[k], s);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) y[m] = s + (float)b4[0];
 }
 
 // Column sums: out[n] += sum_m X[m][n] (bias gradients); workgroup (x, y)

@@ -135,9 +135,9 @@ __device__ __forceinline__ float forward16(__amdgpu_buffer_rsrc_t rp, __amdgpu_b
         act_to_bf16(a0, rw, mlp::offB(0), t, g, act[t / 2], 0);
         act_to_bf16(a1, rw, mlp::offB(0), t + 1, g, act[t / 2], 1);
     }
-    // hidden layers 1..3
+    // hidden layers 1..2 (BF16 activations for the next product)
 #pragma unroll 1
-    for (int l = 1; l < 4; ++l) {
+    for (int l = 1; l < 3; ++l) {
         asm volatile("" ::: "memory");
         const int base = (int)(16 * (kPack0 + (int64_t)(l - 1) * kPackL));
         bf16x8 nxt[kSteps];
@@ -157,17 +157,24 @@ __device__ __forceinline__ float forward16(__amdgpu_buffer_rsrc_t rp, __amdgpu_b
 #pragma unroll
         for (int s = 0; s < kSteps; ++s) act[s] = nxt[s];
     }
-    // output layer: sum over the lane's 64 features, then over the 4 groups
+    // hidden layer 3 and the output layer: the FP32 activations of each
+    // output tile go straight into the lane's share of the output dot product
+    asm volatile("" ::: "memory");
     float y = 0.0f;
+    {
+        const int base = (int)(16 * (kPack0 + 2 * kPackL));
 #pragma unroll
-    for (int s = 0; s < kSteps; ++s) {
-        float wa[4], wb[4];
-        load4(rw, g, mlp::kOffW4 + 32 * s, wa);
-        load4(rw, g, mlp::kOffW4 + 32 * s + 16, wb);
+        for (int t = 0; t < kTiles; ++t) {
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            y = __builtin_fmaf((float)act[s][j], wa[j], y);
-            y = __builtin_fmaf((float)act[s][4 + j], wb[j], y);
+            for (int s = 0; s < kSteps; ++s)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load_frag(rp, loff, base + 1024 * (t * kSteps + s)),
+                                                              act[s], acc, 0, 0, 0);
+            float b[4], w4[4];
+            load4(rw, g, mlp::offB(3) + 16 * t, b);
+            load4(rw, g, mlp::kOffW4 + 16 * t, w4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) y = __builtin_fmaf(mlp::silu(acc[i] + b[i]), w4[i], y);
         }
     }
     y += __shfl_xor(y, 16);

@@ -108,9 +108,11 @@ class Surrogate:
         return out
 
     def train(self, u: torch.Tensor, t: torch.Tensor, steps: int, batch: int = 4096,
-              lr: float = 2e-3, lr_min: float = 2e-5, seed: int = 0, log_every: int = 0):
+              lr: float = 2e-3, lr_min: float = 2e-5, seed: int = 0, log_every: int = 0,
+              verbose: bool = False):
         """Adam with cosine learning-rate decay over `steps` minibatches; the
-        dataset is reshuffled every epoch.  Returns the loss history."""
+        dataset is reshuffled every epoch.  Returns the loss history (and
+        prints each entry as it is taken when verbose)."""
         n = u.shape[0]
         g = torch.Generator(device="cuda")
         g.manual_seed(seed)
@@ -138,6 +140,8 @@ class Surrogate:
             if log_every and (k + 1) % log_every == 0:
                 hist.append((k + 1, float(loss) / log_every, time.perf_counter() - t0))
                 loss.zero_()
+                if verbose:
+                    print(f"step {hist[-1][0]:7d}  mse {hist[-1][1]:.3e}  {hist[-1][2]:7.1f} s", flush=True)
         torch.cuda.synchronize()
         return hist
 
@@ -195,11 +199,10 @@ def main(argv=None):
     steps = int(a.epochs * n / a.batch)
     sg = Surrogate(a.model, seed=a.seed)
     t0 = time.perf_counter()
-    hist = sg.train(u, t, steps=steps, batch=a.batch, lr=a.lr, seed=a.seed,
-                    log_every=max(1, steps // 20))
+    print(f"training {a.model}: {n} samples, {steps} steps of {a.batch}", flush=True)
+    sg.train(u, t, steps=steps, batch=a.batch, lr=a.lr, seed=a.seed,
+             log_every=max(1, min(steps // 20, 5000)), verbose=True)
     t_train = time.perf_counter() - t0
-    for k, loss, el in hist:
-        print(f"step {k:7d}  mse(ln P) {loss:.3e}  {el:7.1f} s", flush=True)
     ev = sg.evaluate(uv, tv)
     meta = {"n": n, "epochs": a.epochs, "batch": a.batch, "lr": a.lr, "seed": a.seed,
             "steps": steps, "dataset_s": round(t_data, 2), "train_s": round(t_train, 2),

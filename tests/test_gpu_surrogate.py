@@ -20,8 +20,8 @@ NTHREADS = max(1, min(16, os.cpu_count() or 1))
 # over their whole input box (ln P root-mean-square; 99th percentile of the
 # relative error of P).  The parallelepiped's isotropic average keeps deep
 # minima at large q for near-cubic shapes, which dominate its error.
-SURROGATE_LNP_RMS = {"parallelepiped": 4.5e-2, "spheroid": 5e-3}
-SURROGATE_P99 = {"parallelepiped": 0.2, "spheroid": 2e-2}
+SURROGATE_LNP_RMS = {"parallelepiped": 3e-2, "spheroid": 2e-3}
+SURROGATE_P99 = {"parallelepiped": 0.13, "spheroid": 7e-3}
 
 
 def _ln_pref(model, xi):
