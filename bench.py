@@ -135,10 +135,15 @@ def parse():
 def cpu_baseline(params, seed, target_s):
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
+    # calibrate the sample size on a probe long enough to hide thread start-up
     n = 200_000
-    t0 = time.perf_counter()
-    oracle.trace(params, n, seed, nthreads=threads)
-    dt = time.perf_counter() - t0
+    while True:
+        t0 = time.perf_counter()
+        oracle.trace(params, n, seed, nthreads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 or n >= 1 << 27:
+            break
+        n *= 4
     rate = n / max(dt, 1e-9)
     n_s = int(max(n, min(rate * target_s, 2e9)))
     t0 = time.perf_counter()

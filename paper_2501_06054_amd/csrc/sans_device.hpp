@@ -480,9 +480,12 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
 // st = sqrt(1 - mu^2).  The parallelepiped's amplitude is a product of one
 // factor per axis, so its C factor (which depends on mu only) leaves the
 // inner beta sum: <F^2> = sum_i w_i F_C(mu_i)^2 sum_l w_l F_A^2 F_B^2.
+// part/nparts: this call sums only every nparts-th node of the outermost
+// loop with more than one node (sizes if there are several, else mu),
+// starting at part; the nparts partial sums add up to the average.
 template <int KIND>
 __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* lq, float q,
-                                              const float qv[3])
+                                              const float qv[3], int part = 0, int nparts = 1)
 {
     const int n = a.quad_n, ny = a.quad_ny;
     const float* mu = lq;
@@ -499,8 +502,11 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* l
         qb0 = qv[0] * a.fB[0] + qv[1] * a.fB[1] + qv[2] * a.fB[2];
         qc0 = qv[0] * a.fC[0] + qv[1] * a.fC[1] + qv[2] * a.fC[2];
     }
+    const bool split_sizes = ny > 1;
+    const int j0 = split_sizes ? part : 0, jstep = split_sizes ? nparts : 1;
+    const int i0 = split_sizes ? 0 : part, istep = split_sizes ? 1 : nparts;
     float total = 0.0f;
-    for (int j = 0; j < ny; ++j) {
+    for (int j = j0; j < ny; j += jstep) {
         const float y = ys[j];
         float s[3];
 #pragma unroll
@@ -508,16 +514,16 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* l
         float avg = 0.0f;
         if (a.quad_dims == 0) {
             const float f = amplitude_f<KIND>(a, s, q, qa0, qb0, qc0);
-            avg = f * f;
+            avg = i0 == 0 ? f * f : 0.0f;
         } else if (a.quad_dims == 1) {
-            for (int i = 0; i < n; ++i) {
+            for (int i = i0; i < n; i += istep) {
                 const float f = amplitude_f<KIND>(a, s, q, q * stt[i], 0.0f, q * mu[i]);
                 avg = __builtin_fmaf(wmu[i], f * f, avg);
             }
         } else if constexpr (KIND == kParallelepiped) {
             const float f0 = a.contrast * s[0] * s[1] * s[2];
             const float ha = 0.5f * q * s[0], hb = 0.5f * q * s[1], hc = 0.5f * q * s[2];
-            for (int i = 0; i < n; ++i) {
+            for (int i = i0; i < n; i += istep) {
                 const float fc = sinc_f(hc * mu[i]);
                 const float xa = ha * stt[i], xb = hb * stt[i];
                 float inner = 0.0f;
@@ -529,7 +535,7 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* l
             }
             avg *= f0 * f0;
         } else {
-            for (int i = 0; i < n; ++i) {
+            for (int i = i0; i < n; i += istep) {
                 const float qst = q * stt[i];
                 const float qc = q * mu[i];
                 float inner = 0.0f;
@@ -553,11 +559,12 @@ struct Event {
 };
 
 // Traces neutron i.  tab_size/tab_norm point to the LDS copies of the
-// tables; lq to the LDS copy of the quadrature nodes (QUAD mode).
+// tables; lq to the LDS copy of the quadrature nodes (QUAD mode; with
+// nparts > 1 the weight is this part's share of the exact average).
 template <int KIND, int MODE>
 __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
                                                const double* tab_size, const double* tab_norm,
-                                               const float* lq)
+                                               const float* lq, int part = 0, int nparts = 1)
 {
     Event ev{-1, 0.0f, 0.0f};
     const uint32_t ilo = (uint32_t)i, ihi = (uint32_t)(i >> 32);
@@ -670,7 +677,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
         f2 = f * f;
     } else if constexpr (MODE == 1) {
         const float qv[3] = {(float)qvd[0], (float)qvd[1], (float)qvd[2]};
-        f2 = quad_average<KIND>(a, lq, q, qv);
+        f2 = quad_average<KIND>(a, lq, q, qv, part, nparts);
     } else {
         // MODE 2 (surrogate): the caller multiplies by the network's <F^2>
         f2 = 1.0f;

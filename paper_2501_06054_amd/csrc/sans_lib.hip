@@ -364,8 +364,12 @@ struct SchulzJob {
     unsigned long long out;  // offset of the table in the output array
 };
 
+// Gauss-Legendre nodes on [-1, 1]: 16 points for the panels of the CDF, 4
+// for the Newton steps inside one panel (a panel is about 1/4096 of the
+// support: the 4-point rule is exact to rounding there).
 struct GL16 {
     double x[16], w[16];
+    double x4[4], w4[4];
 };
 
 __device__ __forceinline__ double schulz_pdf_d(double y, double a, double lnorm)
@@ -380,6 +384,15 @@ __device__ __forceinline__ double pdf_integral(double lo, double hi, double a, d
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) s = __builtin_fma(g.w[i], schulz_pdf_d(__builtin_fma(h, g.x[i], c), a, lnorm), s);
+    return h * s;
+}
+
+__device__ __forceinline__ double pdf_integral4(double lo, double hi, double a, double lnorm, const GL16& g)
+{
+    const double h = 0.5 * (hi - lo), c = 0.5 * (hi + lo);
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s = __builtin_fma(g.w4[i], schulz_pdf_d(__builtin_fma(h, g.x4[i], c), a, lnorm), s);
     return h * s;
 }
 
@@ -423,7 +436,7 @@ __global__ __launch_bounds__(kSchulzBlock) void k_schulz_tables(const SchulzJob*
         double ylo = j * dy, yhi = (j + 1) * dy;
         double y = ylo + (u - cdf[j]) / fmax(cdf[j + 1] - cdf[j], 1e-300) * dy;
         for (int it = 0; it < 60; ++it) {
-            const double gval = cdf[j] + pdf_integral(j * dy, y, jb.a, jb.lnorm, g) - u;
+            const double gval = cdf[j] + pdf_integral4(j * dy, y, jb.a, jb.lnorm, g) - u;
             if (gval > 0.0) yhi = y; else ylo = y;
             const double f = schulz_pdf_d(y, jb.a, jb.lnorm);
             double yn = f > 0.0 ? y - gval / f : 0.5 * (ylo + yhi);
@@ -543,12 +556,14 @@ __global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const m
         __syncthreads();
         float y = 0.0f;
 #pragma unroll 1
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < 4; c += 2) {
             // the weight loads must not be hoisted out of this loop (they
             // would occupy hundreds of registers): opaque memory barrier
             asm volatile("" ::: "memory");
-            const float yc = sur::forward16(rp, rw, xs, c);
-            if ((lane >> 4) == c) y = yc;
+            float yc[2];
+            sur::forward32(rp, rw, xs, c, yc);
+            if ((lane >> 4) == c) y = yc[0];
+            if ((lane >> 4) == c + 1) y = yc[1];
         }
         __syncthreads();
         if (in_dom) {
@@ -562,7 +577,9 @@ __global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const m
     }
 }
 
-// Exact (quadrature) pass over the queued neutrons.
+// Exact (quadrature) pass over the queued neutrons: one wave per neutron,
+// its 64 lanes share the quadrature nodes and add their partial weights (the
+// queue holds few neutrons, each costing thousands of node evaluations).
 template <int KIND>
 __global__ __launch_bounds__(kBlock) void k_trace_queue(const TraceArgs a, LdsLayout lay,
                                                         const unsigned long long* queue, const unsigned* qcount,
@@ -572,10 +589,14 @@ __global__ __launch_bounds__(kBlock) void k_trace_queue(const TraceArgs a, LdsLa
     const LdsPtrs lp = stage_all(a, lay, lds_d);
     __syncthreads();
     const unsigned nq = *qcount;
-    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += gridDim.x * blockDim.x) {
-        const Event ev = trace_neutron<KIND, 1>(a, queue[i], lp.tsize, lp.tnorm, lp.lq);
-        if (ev.pixel >= 0)
-            __hip_atomic_fetch_add(det + ev.pixel, (double)ev.w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int lane = threadIdx.x & 63;
+    const unsigned waves = gridDim.x * (blockDim.x / 64);
+    for (unsigned i = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); i < nq; i += waves) {
+        const Event ev = trace_neutron<KIND, 1>(a, queue[i], lp.tsize, lp.tnorm, lp.lq, lane, 64);
+        float w = ev.w;
+        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
+        if (lane == 0 && ev.pixel >= 0)
+            __hip_atomic_fetch_add(det + ev.pixel, (double)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -896,7 +917,10 @@ const GL16& gl16_nodes()
 {
     static GL16 g;
     static std::once_flag once;
-    std::call_once(once, [] { host::gauss_legendre(16, g.x, g.w); });
+    std::call_once(once, [] {
+        host::gauss_legendre(16, g.x, g.w);
+        host::gauss_legendre(4, g.x4, g.w4);
+    });
     return g;
 }
 
@@ -1528,9 +1552,9 @@ int sans_debug_valu_rates(double* rates, void* stream)
     const int per_step[6] = {2, 2, 1, 1, 1, 1};
     for (int k = 0; k < 6 && e == hipSuccess; ++k) {
         hipLaunchKernelGGL(probes[k], dim3(blocks), dim3(threads), 0, s, out, 3u);   // warm
-        hipEventRecord(e0, s);
+        (void)hipEventRecord(e0, s);
         hipLaunchKernelGGL(probes[k], dim3(blocks), dim3(threads), 0, s, out, 5u);
-        hipEventRecord(e1, s);
+        (void)hipEventRecord(e1, s);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.0f;

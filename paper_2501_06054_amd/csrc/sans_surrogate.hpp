@@ -1,7 +1,8 @@
 // sans_surrogate.hpp -- the surrogate network inside the tracer (gfx950).
 //
-// Every wave evaluates the network for its own 64 neutrons, 16 at a time,
-// with the activations held in registers from layer to layer:
+// Every wave evaluates the network for its own 64 neutrons, 32 at a time
+// (two column groups of 16 sharing each weight fragment), with the
+// activations held in registers from layer to layer:
 //   D[16 features][16 samples] += A[16 features][32 inputs] * B[32 inputs][16 samples]
 // (v_mfma_f32_16x16x32_bf16).  Lane (g = lane/16, r = lane%16) holds, for
 // output tile t, the features 16t + 4g + i (i = 0..3) of sample r.  The
@@ -97,91 +98,136 @@ __device__ __forceinline__ void load4(__amdgpu_buffer_rsrc_t r, int g, int64_t e
     v[3] = __uint_as_float(hi & 0xFFFF0000u);
 }
 
-// Bias + SiLU on an accumulator tile, converted to the next B operand half.
-__device__ __forceinline__ void act_to_bf16(const f32x4& acc, __amdgpu_buffer_rsrc_t rw, int64_t boff, int t,
-                                            int g, bf16x8& dst, int half)
+// Orders the evaluation: the value is complete (in registers) at this point of
+// the instruction stream, so that the scheduler does not keep dozens of
+// independent accumulators live by running ahead.
+__device__ __forceinline__ void settle(bf16x8& v) { asm volatile("" : "+v"(v)); }
+
+// Bias + SiLU on an accumulator tile (biases b of the lane's 4 features),
+// converted to one half of the next B operand.
+__device__ __forceinline__ void act_to_bf16(const f32x4& acc, const float b[4], bf16x8& dst, int half)
 {
-    float b[4];
-    load4(rw, g, boff + 16 * t, b);
 #pragma unroll
     for (int i = 0; i < 4; ++i) dst[4 * half + i] = (__bf16)mlp::silu(acc[i] + b[i]);
 }
 
-// Network output for the 16 samples of column group c of this wave.  xs:
-// this wave's inputs in LDS, [64][8] floats.  Returns, in every lane with
-// g == c, the output for sample 16c + r (lane 16c + r).
-__device__ __forceinline__ float forward16(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rw, const float* xs,
-                                           int c)
+// Network outputs for the 32 samples of column groups c0 and c0 + 1 of this
+// wave (samples 16 c0 + r and 16 (c0 + 1) + r).  Every weight fragment is
+// loaded once and applied to both groups, which halves the weight traffic
+// from L2 per sample.  xs: this wave's inputs in LDS, [64][8] floats.
+// Returns, in every lane (g, r), y[0] for sample 16 c0 + r and y[1] for
+// sample 16 (c0 + 1) + r.
+__device__ __forceinline__ void forward32(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rw, const float* xs,
+                                          int c0, float y[2])
 {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
     const int loff = 16 * lane;
-    // input operand: feature perm_k(g, j) of sample 16c + r: hi parts of the
-    // 8 inputs, then their lo parts, then zeros
-    bf16x8 b0;
+    // input operands: feature perm_k(g, j) of each group's sample: hi parts of
+    // the 8 inputs, then their lo parts, then zeros
+    bf16x8 b0[2];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int k = perm_k(g, j);
-        const float xv = k < 2 * kIn ? xs[(16 * c + r) * kIn + (k % kIn)] : 0.0f;
-        b0[j] = k < kIn ? mlp::bf16_hi(xv) : k < 2 * kIn ? mlp::bf16_lo(xv) : (__bf16)0.0f;
-    }
-    bf16x8 act[kSteps];
+    for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = perm_k(g, j);
+            const float xv = k < 2 * kIn ? xs[(16 * (c0 + gi) + r) * kIn + (k % kIn)] : 0.0f;
+            b0[gi][j] = k < kIn ? mlp::bf16_hi(xv) : k < 2 * kIn ? mlp::bf16_lo(xv) : (__bf16)0.0f;
+        }
+    bf16x8 act[2][kSteps];
     // layer 0
 #pragma unroll
     for (int t = 0; t < kTiles; t += 2) {
-        f32x4 a0 = {0.0f, 0.0f, 0.0f, 0.0f}, a1 = {0.0f, 0.0f, 0.0f, 0.0f};
-        a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load_frag(rp, loff, 1024 * t), b0, a0, 0, 0, 0);
-        a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load_frag(rp, loff, 1024 * (t + 1)), b0, a1, 0, 0, 0);
-        act_to_bf16(a0, rw, mlp::offB(0), t, g, act[t / 2], 0);
-        act_to_bf16(a1, rw, mlp::offB(0), t + 1, g, act[t / 2], 1);
+        asm volatile("" ::: "memory");
+        const bf16x8 fa = load_frag(rp, loff, 1024 * t), fb = load_frag(rp, loff, 1024 * (t + 1));
+        float ba[4], bb[4];
+        load4(rw, g, mlp::offB(0) + 16 * t, ba);
+        load4(rw, g, mlp::offB(0) + 16 * (t + 1), bb);
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi) {
+            const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+            const f32x4 a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, b0[gi], z, 0, 0, 0);
+            const f32x4 a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb, b0[gi], z, 0, 0, 0);
+            act_to_bf16(a0, ba, act[gi][t / 2], 0);
+            act_to_bf16(a1, bb, act[gi][t / 2], 1);
+            settle(act[gi][t / 2]);
+        }
     }
     // hidden layers 1..2 (BF16 activations for the next product)
 #pragma unroll 1
     for (int l = 1; l < 3; ++l) {
         asm volatile("" ::: "memory");
         const int base = (int)(16 * (kPack0 + (int64_t)(l - 1) * kPackL));
-        bf16x8 nxt[kSteps];
+        bf16x8 nxt[2][kSteps];
 #pragma unroll
         for (int t = 0; t < kTiles; t += 2) {
-            f32x4 a0 = {0.0f, 0.0f, 0.0f, 0.0f}, a1 = {0.0f, 0.0f, 0.0f, 0.0f};
+            // keeps the fragment loads of later tiles from being hoisted here
+            asm volatile("" ::: "memory");
+            f32x4 acc[2][2];
+#pragma unroll
+            for (int gi = 0; gi < 2; ++gi) acc[gi][0] = acc[gi][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int s = 0; s < kSteps; ++s) {
-                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load_frag(rp, loff, base + 1024 * (t * kSteps + s)),
-                                                             act[s], a0, 0, 0, 0);
-                a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    load_frag(rp, loff, base + 1024 * ((t + 1) * kSteps + s)), act[s], a1, 0, 0, 0);
+                // at most half a tile pair's fragments in flight (registers)
+                if (s == kSteps / 2) asm volatile("" ::: "memory");
+                const bf16x8 fa = load_frag(rp, loff, base + 1024 * (t * kSteps + s));
+                const bf16x8 fb = load_frag(rp, loff, base + 1024 * ((t + 1) * kSteps + s));
+#pragma unroll
+                for (int gi = 0; gi < 2; ++gi) {
+                    acc[gi][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, act[gi][s], acc[gi][0], 0, 0, 0);
+                    acc[gi][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb, act[gi][s], acc[gi][1], 0, 0, 0);
+                }
             }
-            act_to_bf16(a0, rw, mlp::offB(l), t, g, nxt[t / 2], 0);
-            act_to_bf16(a1, rw, mlp::offB(l), t + 1, g, nxt[t / 2], 1);
+            float ba[4], bb[4];
+            load4(rw, g, mlp::offB(l) + 16 * t, ba);
+            load4(rw, g, mlp::offB(l) + 16 * (t + 1), bb);
+#pragma unroll
+            for (int gi = 0; gi < 2; ++gi) {
+                act_to_bf16(acc[gi][0], ba, nxt[gi][t / 2], 0);
+                act_to_bf16(acc[gi][1], bb, nxt[gi][t / 2], 1);
+                settle(nxt[gi][t / 2]);
+            }
         }
 #pragma unroll
-        for (int s = 0; s < kSteps; ++s) act[s] = nxt[s];
+        for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+            for (int s = 0; s < kSteps; ++s) act[gi][s] = nxt[gi][s];
     }
     // hidden layer 3 and the output layer: the FP32 activations of each
     // output tile go straight into the lane's share of the output dot product
     asm volatile("" ::: "memory");
-    float y = 0.0f;
+    y[0] = y[1] = 0.0f;
     {
         const int base = (int)(16 * (kPack0 + 2 * kPackL));
 #pragma unroll
         for (int t = 0; t < kTiles; ++t) {
-            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            asm volatile("" ::: "memory");
+            f32x4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
 #pragma unroll
-            for (int s = 0; s < kSteps; ++s)
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load_frag(rp, loff, base + 1024 * (t * kSteps + s)),
-                                                              act[s], acc, 0, 0, 0);
+            for (int s = 0; s < kSteps; ++s) {
+                const bf16x8 f = load_frag(rp, loff, base + 1024 * (t * kSteps + s));
+#pragma unroll
+                for (int gi = 0; gi < 2; ++gi)
+                    acc[gi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f, act[gi][s], acc[gi], 0, 0, 0);
+            }
             float b[4], w4[4];
             load4(rw, g, mlp::offB(3) + 16 * t, b);
             load4(rw, g, mlp::kOffW4 + 16 * t, w4);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) y = __builtin_fmaf(mlp::silu(acc[i] + b[i]), w4[i], y);
+            for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) y[gi] = __builtin_fmaf(mlp::silu(acc[gi][i] + b[i]), w4[i], y[gi]);
+            asm volatile("" : "+v"(y[0]), "+v"(y[1]));
         }
     }
-    y += __shfl_xor(y, 16);
-    y += __shfl_xor(y, 32);
     float b4[4];
     load4(rw, 0, mlp::kOffB4, b4);
-    return y + b4[0];
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi) {
+        y[gi] += __shfl_xor(y[gi], 16);
+        y[gi] += __shfl_xor(y[gi], 32);
+        y[gi] += b4[0];
+    }
 }
 
 }  // namespace sur
