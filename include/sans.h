@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define SANS_ABI_VERSION 1u
+#define SANS_ABI_VERSION 2u
 
 /* Status codes. */
 #define SANS_OK 0
@@ -88,12 +88,23 @@ typedef enum {
                                        phi, Psi ~ U[0,2pi] (not isotropic)       */
 } sans_orient;
 
+/* Size distribution of the polydisperse sizes (relative size y, mean 1 for
+ * Schulz; the mode at 1 for the Gaussian). */
+typedef enum {
+    SANS_POLY_SCHULZ = 0,   /* Schulz (Gamma) of relative width poly             */
+    SANS_POLY_GAUSSIAN = 1  /* the paper's rule (Methods, "Polydispersity and
+                               orientational distributions", Eq. (8)): y ~
+                               N(1, poly^2) redrawn until positive, i.e. the
+                               normal restricted to y > 0, drawn by inverse CDF */
+} sans_poly;
+
 /* Tally strategies (all give the same detector up to FP64 summation order).
  * AUTO takes LDS when the whole detector (plus the tables) fits in a
  * workgroup's 160 KiB of LDS, else BINNED.  Requests for det_w2/det_count use
  * the atomic path (GLOBAL, or XCD when asked for). */
 typedef enum {
-    SANS_TALLY_AUTO = 0,   /* library choice                                      */
+    SANS_TALLY_AUTO = 0,   /* library choice: GLOBAL in quadrature mode, else LDS
+                              when the detector fits in 128 KiB, else BINNED     */
     SANS_TALLY_GLOBAL = 1, /* one FP64 global atomic per detected neutron          */
     SANS_TALLY_LDS = 2,    /* workgroup-private FP64 histogram of the detector in
                               LDS; partial histograms summed by a second kernel   */
@@ -138,8 +149,8 @@ typedef struct {
     double phi;              /* particle volume fraction (number density phi/<V>) */
     double sq_phi;           /* hard-sphere volume fraction, in [0, 0.6)       */
     double sq_radius;        /* hard-sphere radius                             */
-    double poly;             /* Schulz relative width sigma/mean of the size draw
-                                y (mean 1); 0 = monodisperse                   */
+    double poly;             /* relative width sigma of the size draw y (see
+                                poly_kind); 0 = monodisperse                   */
     int32_t poly_mask;       /* bit k set: size[k] is multiplied by y (the core-
                                 shell shell never is)                          */
     int32_t table_size;      /* knots of the inverse-CDF tables (64..8192)     */
@@ -153,6 +164,8 @@ typedef struct {
     int32_t nx, ny;
     int32_t quad_n;          /* Gauss-Legendre order of SANS_MODE_QUAD (<= 256) */
     int32_t tally;           /* sans_tally                                     */
+    int32_t poly_kind;       /* sans_poly                                      */
+    int32_t reserved;        /* 0                                              */
 } sans_params;
 
 typedef struct sans_model_s* sans_model_t;

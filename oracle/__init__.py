@@ -21,6 +21,7 @@ SO = os.path.join(HERE, "liboracle.so")
 KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelepiped": 4}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
+POLY_KIND = {"schulz": 0, "gaussian": 1}
 
 
 class OrcParams(C.Structure):
@@ -37,6 +38,7 @@ class OrcParams(C.Structure):
         ("det_w", C.c_double), ("det_h", C.c_double), ("det_z", C.c_double),
         ("nx", C.c_int32), ("ny", C.c_int32),
         ("table_size", C.c_int32), ("quad_n", C.c_int32),
+        ("poly_kind", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -67,7 +69,7 @@ def lib():
         for f in ("orc_normal_quantile",):
             getattr(L, f).argtypes = [d]
             getattr(L, f).restype = d
-        for f in ("orc_schulz_quantile", "orc_gamma_p", "orc_py_g_over_x_direct"):
+        for f in ("orc_schulz_quantile", "orc_truncnorm_quantile", "orc_gamma_p", "orc_py_g_over_x_direct"):
             getattr(L, f).argtypes = [d, d]
             getattr(L, f).restype = d
         for f in ("orc_sph", "orc_lambda1", "orc_sinc"):
@@ -77,6 +79,9 @@ def lib():
         L.orc_py_sq.restype = d
         L.orc_py_series.argtypes = [d, i32, P(d)]
         L.orc_table_normal.argtypes = [i32, P(d)]
+        L.orc_table_truncnorm.argtypes = [i32, d, P(d)]
+        L.orc_size_moment.argtypes = [P(OrcParams), i32]
+        L.orc_size_moment.restype = d
         L.orc_table_schulz.argtypes = [i32, d, P(d)]
         L.orc_table_lookup.argtypes = [P(d), i32, d]
         L.orc_table_lookup.restype = d
@@ -126,6 +131,7 @@ def to_params(p: dict) -> OrcParams:
     o.nx, o.ny = int(p["nx"]), int(p["ny"])
     o.table_size = int(p["table_size"])
     o.quad_n = int(p["quad_n"])
+    o.poly_kind = POLY_KIND[p.get("poly_kind", "schulz")]
     return o
 
 
@@ -155,6 +161,23 @@ def normal_quantile(u: float) -> float:
 
 def schulz_quantile(u: float, p: float) -> float:
     return lib().orc_schulz_quantile(u, p)
+
+
+def truncnorm_quantile(u: float, p: float) -> float:
+    """Quantile of N(1, p^2) restricted to positive values."""
+    return lib().orc_truncnorm_quantile(u, p)
+
+
+def table_truncnorm(M: int, p: float) -> np.ndarray:
+    out = np.zeros(M)
+    lib().orc_table_truncnorm(M, p, _ptr(out, C.c_double))
+    return out
+
+
+def size_moment(p: dict, k: int) -> float:
+    """<y^k> of the parameter set's size distribution."""
+    o = to_params(p)
+    return lib().orc_size_moment(C.byref(o), k)
 
 
 def gamma_p(a: float, x: float) -> float:

@@ -50,7 +50,7 @@ typedef struct {
     double phi;            /* particle volume fraction, n = phi/<V>          */
     double sq_phi;         /* hard-sphere volume fraction; 0 -> S = 1        */
     double sq_radius;      /* hard-sphere radius                             */
-    double poly;           /* Schulz relative width sigma/mean; 0 -> none    */
+    double poly;           /* relative width sigma/mean; 0 -> none           */
     int32_t poly_mask;     /* bit k: size[k] is scaled by the size draw      */
     int32_t orient_kind;   /* 0 fixed, 1 gaussian, 2 isotropic, 3 uniform angles */
     double orient_mean[3]; /* theta, phi, Psi                                */
@@ -63,6 +63,9 @@ typedef struct {
     int32_t nx, ny;
     int32_t table_size;    /* inverse-CDF knots (M)                          */
     int32_t quad_n;        /* Gauss-Legendre order of the exact average      */
+    int32_t poly_kind;     /* size distribution: 0 Schulz, 1 Gaussian kept
+                              only where the size is positive                */
+    int32_t pad_;
 } orc_params;
 
 /* Surrogate mode (mode 2): a network replaces the exact average; set with
@@ -184,6 +187,17 @@ double orc_schulz_quantile(double u, double p)
     return 0.5 * (lo + hi);
 }
 
+/* The paper's size distribution (Methods, "Polydispersity and orientational
+ * distributions", Eq. (8)): y ~ N(1, p^2), redrawn until positive, i.e. the
+ * normal distribution restricted to y > 0.  Its quantile maps u into the
+ * part of the normal CDF above y = 0: y = 1 + p Phi^-1(Phi(-1/p) + u (1 -
+ * Phi(-1/p))). */
+double orc_truncnorm_quantile(double u, double p)
+{
+    double c0 = normal_cdf(-1.0 / p);
+    return 1.0 + p * orc_normal_quantile(c0 + u * (1.0 - c0));
+}
+
 /* Inverse-CDF table: knots y_k = F^-1((k + 1/2)/M), k = 0 .. M-1. */
 void orc_table_normal(int32_t M, double* knots)
 {
@@ -193,6 +207,18 @@ void orc_table_normal(int32_t M, double* knots)
 void orc_table_schulz(int32_t M, double p, double* knots)
 {
     for (int k = 0; k < M; ++k) knots[k] = orc_schulz_quantile((k + 0.5) / M, p);
+}
+
+void orc_table_truncnorm(int32_t M, double p, double* knots)
+{
+    for (int k = 0; k < M; ++k) knots[k] = orc_truncnorm_quantile((k + 0.5) / M, p);
+}
+
+/* The size table of a parameter set (Schulz or positive Gaussian). */
+static void size_table(const orc_params* p, double* knots)
+{
+    if (p->poly_kind == 1) orc_table_truncnorm(p->table_size, p->poly, knots);
+    else orc_table_schulz(p->table_size, p->poly, knots);
 }
 
 /* Table lookup: s = u M - 1/2, k = clamp(floor(s), 0, M-2), linear
@@ -384,28 +410,53 @@ static double schulz_moment(double p, int k)
     return m;
 }
 
+/* Moments <y^k> of N(1, p^2) restricted to y > 0 (mean mu = 1, sd s = p,
+ * alpha = -1/p, Z = 1 - Phi(alpha)): m_0 = 1, m_1 = mu + s phi(alpha)/Z and,
+ * the lower bound being 0, m_k = mu m_{k-1} + (k - 1) s^2 m_{k-2} (k >= 2). */
+static double truncnorm_moment(double p, int k)
+{
+    if (p <= 0.0) return 1.0;
+    double alpha = -1.0 / p;
+    double z = 1.0 - normal_cdf(alpha);
+    double dens = exp(-0.5 * alpha * alpha) / sqrt(2.0 * ORC_PI);
+    double m0 = 1.0, m1 = 1.0 + p * dens / z;
+    if (k == 0) return m0;
+    for (int j = 2; j <= k; ++j) {
+        double m2 = m1 + (j - 1) * p * p * m0;
+        m0 = m1;
+        m1 = m2;
+    }
+    return m1;
+}
+
+static double size_moment(const orc_params* p, int k)
+{
+    return p->poly_kind == 1 ? truncnorm_moment(p->poly, k) : schulz_moment(p->poly, k);
+}
+
+double orc_size_moment(const orc_params* p, int32_t k) { return size_moment(p, k); }
+
 /* Number-averaged particle volume <V> (n = phi/<V>). */
 double orc_mean_volume(const orc_params* p)
 {
-    double pr = p->poly;
     const double* s = p->size;
     int b0 = p->poly_mask & 1, b1 = p->poly_mask >> 1 & 1, b2 = p->poly_mask >> 2 & 1;
     switch (p->kind) {
     case 0:
-        return vol_sphere(s[0]) * schulz_moment(pr, b0 ? 3 : 0);
+        return vol_sphere(s[0]) * size_moment(p, b0 ? 3 : 0);
     case 1: {
         double r = s[0], t = p->shell;
         if (!b0) return vol_sphere(r + t);
-        return 4.0 / 3.0 * ORC_PI * (r * r * r * schulz_moment(pr, 3)
-                                      + 3.0 * r * r * t * schulz_moment(pr, 2)
-                                      + 3.0 * r * t * t * schulz_moment(pr, 1) + t * t * t);
+        return 4.0 / 3.0 * ORC_PI * (r * r * r * size_moment(p, 3)
+                                      + 3.0 * r * r * t * size_moment(p, 2)
+                                      + 3.0 * r * t * t * size_moment(p, 1) + t * t * t);
     }
     case 2:
-        return ORC_PI * s[0] * s[0] * s[1] * schulz_moment(pr, 2 * b0 + b1);
+        return ORC_PI * s[0] * s[0] * s[1] * size_moment(p, 2 * b0 + b1);
     case 3:
-        return 4.0 / 3.0 * ORC_PI * s[0] * s[1] * s[2] * schulz_moment(pr, b0 + b1 + b2);
+        return 4.0 / 3.0 * ORC_PI * s[0] * s[1] * s[2] * size_moment(p, b0 + b1 + b2);
     case 4:
-        return s[0] * s[1] * s[2] * schulz_moment(pr, b0 + b1 + b2);
+        return s[0] * s[1] * s[2] * size_moment(p, b0 + b1 + b2);
     }
     return 0.0;
 }
@@ -471,6 +522,20 @@ static double schulz_pdf(double y, double p)
     return exp(a * log(a) + (a - 1.0) * log(y) - a * y - lgamma(a));
 }
 
+/* Density of the positive Gaussian (up to its constant normalisation: the
+ * quadrature weights are normalised to sum 1). */
+static double truncnorm_pdf(double y, double p)
+{
+    if (y <= 0.0) return 0.0;
+    double d = (y - 1.0) / p;
+    return exp(-0.5 * d * d);
+}
+
+static double size_pdf(const orc_params* p, double y)
+{
+    return p->poly_kind == 1 ? truncnorm_pdf(y, p->poly) : schulz_pdf(y, p->poly);
+}
+
 /* Exact average <F^2>(q) that replaces the per-event size and orientation
  * draws in quadrature mode: Schulz size average by quad_n Gauss-Legendre
  * nodes on y in [max(0, 1-6p), 1+8p] (weights normalised to the quadrature
@@ -490,13 +555,14 @@ static double pq_avg_nodes(const orc_params* p, double q, const double qvec[3],
     ys[0] = 1.0;
     yw[0] = 1.0;
     if (p->poly > 0.0) {
-        double lo = 1.0 - 6.0 * p->poly, hi = 1.0 + 8.0 * p->poly;
+        /* Schulz: [1 - 6p, 1 + 8p] (right-skewed); Gaussian: 1 -+ 6p */
+        double lo = 1.0 - 6.0 * p->poly, hi = 1.0 + (p->poly_kind == 1 ? 6.0 : 8.0) * p->poly;
         if (lo < 0.0) lo = 0.0;
         double norm = 0.0;
         ny = n;
         for (int j = 0; j < n; ++j) {
             ys[j] = 0.5 * (hi - lo) * gx[j] + 0.5 * (hi + lo);
-            yw[j] = 0.5 * (hi - lo) * gw[j] * schulz_pdf(ys[j], p->poly);
+            yw[j] = 0.5 * (hi - lo) * gw[j] * size_pdf(p, ys[j]);
             norm += yw[j];
         }
         for (int j = 0; j < n; ++j) yw[j] /= norm;
@@ -600,7 +666,7 @@ static int ctx_init(orc_ctx* cx, const orc_params* p)
     int M = p->table_size;
     if (p->mode == 0 && p->poly > 0.0) {
         cx->tab_size = (double*)malloc(sizeof(double) * M);
-        orc_table_schulz(M, p->poly, cx->tab_size);
+        size_table(p, cx->tab_size);
     }
     if (p->mode == 0 && p->orient_kind == 1) {
         cx->tab_norm = (double*)malloc(sizeof(double) * M);
@@ -1026,6 +1092,7 @@ static double surrogate_f2(const orc_params* p, double q, int* in_domain)
     double x[4] = {log(q * p->size[0]), log(p->size[1] / p->size[0]), log(p->size[2] / p->size[0]), p->poly};
     *in_domain = 0;
     if (!g_sur_set) return 0.0;
+    if (p->poly_kind != 0 && p->poly > 0.0) return 0.0;   /* trained on Schulz sizes only */
     double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < 4; ++k) {
         if (!(x[k] >= g_sur_lo[k] - (k ? 1e-6 : 0.0) && x[k] <= g_sur_hi[k] + (k ? 1e-6 : 0.0))) return 0.0;

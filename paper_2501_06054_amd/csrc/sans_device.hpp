@@ -89,7 +89,7 @@ struct TraceArgs {
     const double* tab_norm;       // normal quantiles or nullptr
     // exact-average quadrature (QUAD mode), FP32 nodes
     int32_t quad_n, quad_ny, quad_dims;   // orientation nodes, size nodes, 0/1/2-D orientation
-    const float* quad_nodes;      // mu[n] wmu[n] cb[n] sb[n] wb[n] y[ny] wy[ny]
+    const float* quad_nodes;      // mu[n] wmu[n] cb[n] sb[n] wb[n] st[n] y[ny] wy[ny] (global)
     float fsize[3], fshell;       // FP32 copies for the quadrature loop
     float fA[3], fB[3], fC[3];    // fixed-orientation particle axes (FP32)
     // run
@@ -276,11 +276,18 @@ __device__ __forceinline__ float lambda1_f(float x)
     return 2.0f * j1f(x) * rcpf(x);
 }
 
-// sin(x)/x: series below 0.5, else from the reduced phase.
+// sin(x)/x: Taylor series to x^16 below 2 (truncation below 2e-10 there;
+// the sums of the quadrature stay on this branch for the small-angle
+// workloads, so a wave rarely takes both), else from the reduced phase.
+constexpr float kSincSeriesMax = 2.0f;
 __device__ __forceinline__ float sinc_series(float x)
 {
     const float x2 = x * x;
-    float r = SinC<4>::v;
+    float r = SinC<8>::v;
+    r = __builtin_fmaf(r, x2, SinC<7>::v);
+    r = __builtin_fmaf(r, x2, SinC<6>::v);
+    r = __builtin_fmaf(r, x2, SinC<5>::v);
+    r = __builtin_fmaf(r, x2, SinC<4>::v);
     r = __builtin_fmaf(r, x2, SinC<3>::v);
     r = __builtin_fmaf(r, x2, SinC<2>::v);
     r = __builtin_fmaf(r, x2, SinC<1>::v);
@@ -291,7 +298,7 @@ __device__ __forceinline__ float sinc_d(double xd)
 {
     xd = fabs(xd);
     const float x = (float)xd;
-    if (x < 0.5f) return sinc_series(x);
+    if (x < kSincSeriesMax) return sinc_series(x);
     float s, c;
     sincos_phase(xd, s, c);
     return s * rcpf(x);
@@ -300,7 +307,7 @@ __device__ __forceinline__ float sinc_d(double xd)
 __device__ __forceinline__ float sinc_f(float x)
 {
     x = fabsf(x);
-    if (x < 0.5f) return sinc_series(x);
+    if (x < kSincSeriesMax) return sinc_series(x);
     float s, c;
     sincos_f(x, s, c);
     return s * rcpf(x);
@@ -476,15 +483,17 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
 
 // ---------------------------------------------------------------- exact average
 // <F^2>(q) over the Schulz size nodes and (isotropic) the orientation nodes
-// held in LDS: lq = mu[n] wmu[n] cb[n] sb[n] wb[n] st[n] y[ny] wy[ny], with
-// st = sqrt(1 - mu^2).  The parallelepiped's amplitude is a product of one
+// lq = mu[n] wmu[n] cb[n] sb[n] wb[n] st[n] y[ny] wy[ny], with st =
+// sqrt(1 - mu^2), read from global memory: every lane of a wave reads the
+// same node at the same time, so the reads go through the scalar data cache
+// into scalar registers (no LDS traffic, no vector registers for them).  The parallelepiped's amplitude is a product of one
 // factor per axis, so its C factor (which depends on mu only) leaves the
 // inner beta sum: <F^2> = sum_i w_i F_C(mu_i)^2 sum_l w_l F_A^2 F_B^2.
 // part/nparts: this call sums only every nparts-th node of the outermost
 // loop with more than one node (sizes if there are several, else mu),
 // starting at part; the nparts partial sums add up to the average.
 template <int KIND>
-__device__ __forceinline__ float quad_average(const TraceArgs& a, const float* lq, float q,
+__device__ __forceinline__ float quad_average(const TraceArgs& a, const float* __restrict__ lq, float q,
                                               const float qv[3], int part = 0, int nparts = 1)
 {
     const int n = a.quad_n, ny = a.quad_ny;
@@ -516,6 +525,7 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* l
             const float f = amplitude_f<KIND>(a, s, q, qa0, qb0, qc0);
             avg = i0 == 0 ? f * f : 0.0f;
         } else if (a.quad_dims == 1) {
+#pragma unroll 4
             for (int i = i0; i < n; i += istep) {
                 const float f = amplitude_f<KIND>(a, s, q, q * stt[i], 0.0f, q * mu[i]);
                 avg = __builtin_fmaf(wmu[i], f * f, avg);
@@ -527,6 +537,7 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* l
                 const float fc = sinc_f(hc * mu[i]);
                 const float xa = ha * stt[i], xb = hb * stt[i];
                 float inner = 0.0f;
+#pragma unroll 4
                 for (int l = 0; l < n; ++l) {
                     const float g = sinc_f(xa * cb[l]) * sinc_f(xb * sb[l]);
                     inner = __builtin_fmaf(wb[l], g * g, inner);
@@ -677,7 +688,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
         f2 = f * f;
     } else if constexpr (MODE == 1) {
         const float qv[3] = {(float)qvd[0], (float)qvd[1], (float)qvd[2]};
-        f2 = quad_average<KIND>(a, lq, q, qv, part, nparts);
+        f2 = quad_average<KIND>(a, a.quad_nodes, q, qv, part, nparts);
     } else {
         // MODE 2 (surrogate): the caller multiplies by the network's <F^2>
         f2 = 1.0f;

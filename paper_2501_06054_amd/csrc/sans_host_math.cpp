@@ -67,41 +67,6 @@ static double integrate_pdf(double lo, double hi, double a, double lnorm)
     return h * s;
 }
 
-// Schulz quantiles at (k + 1/2)/M.  The CDF is tabulated by integrating the
-// density panel by panel (16-point Gauss-Legendre per panel) and each quantile
-// is then refined inside its panel by safeguarded Newton steps on
-// C(y_j) + int_{y_j}^{y} pdf - u = 0.
-void schulz_table(double p, int M, double* out)
-{
-    const double a = 1.0 / (p * p);
-    const double lnorm = a * std::log(a) - std::lgamma(a);
-    const double ymax = 1.0 + 60.0 * p + 10.0 * p * p;
-    const int P = 8192;
-    const double dy = ymax / P;
-    std::vector<double> cdf(P + 1, 0.0);
-    for (int j = 0; j < P; ++j) cdf[j + 1] = cdf[j] + integrate_pdf(j * dy, (j + 1) * dy, a, lnorm);
-    const double total = cdf[P];
-    for (int k = 0; k < M; ++k) {
-        const double u = (k + 0.5) / M * total;
-        int j = (int)(std::upper_bound(cdf.begin(), cdf.end(), u) - cdf.begin()) - 1;
-        j = std::min(std::max(j, 0), P - 1);
-        double lo = j * dy, hi = (j + 1) * dy;
-        double y = lo + (u - cdf[j]) / std::max(cdf[j + 1] - cdf[j], 1e-300) * dy;
-        for (int it = 0; it < 60; ++it) {
-            const double g = cdf[j] + integrate_pdf(j * dy, y, a, lnorm) - u;
-            if (g > 0.0) hi = y; else lo = y;
-            const double f = schulz_pdf(y, a, lnorm);
-            double yn = (f > 0.0) ? y - g / f : 0.5 * (lo + hi);
-            if (!(yn > lo && yn < hi)) yn = 0.5 * (lo + hi);
-            if (std::fabs(yn - y) <= 1e-16 * y) {
-                y = yn;
-                break;
-            }
-            y = yn;
-        }
-        out[k] = y;
-    }
-}
 
 // Gauss-Legendre nodes (ascending) and weights on [-1, 1]: Newton's method on
 // P_n, evaluated by the Bonnet recurrence, from Tricomi's initial estimate.
@@ -175,14 +140,51 @@ double schulz_moment(double p, int k)
     return std::exp(std::lgamma(a + k) - std::lgamma(a) - k * std::log(a));
 }
 
+// The paper's size distribution (Methods, "Polydispersity and orientational
+// distributions", Eq. (8)) restricted to positive sizes: N(1, p^2) on y > 0.
+// Quantile: 1 + p Phi^-1(Phi(-1/p) + u (1 - Phi(-1/p))).
+double positive_normal_quantile(double u, double p)
+{
+    const double c0 = 0.5 * std::erfc(1.0 / (p * std::sqrt(2.0)));
+    return 1.0 + p * normal_quantile(c0 + u * (1.0 - c0));
+}
+
+// E[y^k] of that distribution by composite Gauss-Legendre quadrature of
+// y^k exp(-(y-1)^2 / 2p^2) over [max(0, 1 - 12p), 1 + 12p] (8 panels of 16
+// nodes), divided by the same quadrature of the density.
+double positive_normal_moment(double p, int k)
+{
+    if (p <= 0.0 || k == 0) return 1.0;
+    double gx[16], gw[16];
+    gauss_legendre(16, gx, gw);
+    const double lo = std::max(0.0, 1.0 - 12.0 * p), hi = 1.0 + 12.0 * p;
+    const int panels = 8;
+    const double h = (hi - lo) / panels;
+    double num = 0.0, den = 0.0;
+    for (int j = 0; j < panels; ++j)
+        for (int i = 0; i < 16; ++i) {
+            const double y = lo + h * (j + 0.5 * (gx[i] + 1.0));
+            const double d = (y - 1.0) / p;
+            const double f = 0.5 * h * gw[i] * std::exp(-0.5 * d * d);
+            num += f * std::pow(y, k);
+            den += f;
+        }
+    return num / den;
+}
+
+double size_moment(int poly_kind, double p, int k)
+{
+    return poly_kind == 1 ? positive_normal_moment(p, k) : schulz_moment(p, k);
+}
+
 // Number-averaged volume of the particle population.
-double mean_volume(int kind, const double size[3], double shell, double poly, int mask)
+double mean_volume(int kind, const double size[3], double shell, double poly, int mask, int poly_kind)
 {
     const bool b0 = mask & 1, b1 = mask & 2, b2 = mask & 4;
     const double c43 = 4.0 / 3.0 * kPiH;
     switch (kind) {
     case 0:
-        return c43 * size[0] * size[0] * size[0] * schulz_moment(poly, b0 ? 3 : 0);
+        return c43 * size[0] * size[0] * size[0] * size_moment(poly_kind, poly, b0 ? 3 : 0);
     case 1: {
         // (y R + t)^3 expanded in powers of y
         const double r = size[0], t = shell;
@@ -190,17 +192,17 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
         double v = 0.0;
         const double binom[4] = {1.0, 3.0, 3.0, 1.0};
         for (int j = 0; j <= 3; ++j)
-            v += binom[j] * std::pow(r, j) * std::pow(t, 3 - j) * schulz_moment(poly, j);
+            v += binom[j] * std::pow(r, j) * std::pow(t, 3 - j) * size_moment(poly_kind, poly, j);
         return c43 * v;
     }
     case 2:
-        return kPiH * size[0] * size[0] * size[1] * schulz_moment(poly, (b0 ? 2 : 0) + (b1 ? 1 : 0));
+        return kPiH * size[0] * size[0] * size[1] * size_moment(poly_kind, poly, (b0 ? 2 : 0) + (b1 ? 1 : 0));
     case 3:
         return c43 * size[0] * size[1] * size[2]
-             * schulz_moment(poly, (b0 ? 1 : 0) + (b1 ? 1 : 0) + (b2 ? 1 : 0));
+             * size_moment(poly_kind, poly, (b0 ? 1 : 0) + (b1 ? 1 : 0) + (b2 ? 1 : 0));
     case 4:
         return size[0] * size[1] * size[2]
-             * schulz_moment(poly, (b0 ? 1 : 0) + (b1 ? 1 : 0) + (b2 ? 1 : 0));
+             * size_moment(poly_kind, poly, (b0 ? 1 : 0) + (b1 ? 1 : 0) + (b2 ? 1 : 0));
     }
     return 0.0;
 }

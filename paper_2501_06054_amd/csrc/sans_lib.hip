@@ -336,8 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_pq_avg(const TraceArgs a, LdsLayout 
                                                    const float* qvec, int64_t n, float* out)
 {
     extern __shared__ double lds_d[];
-    const LdsPtrs lp = stage_all(a, lay, lds_d);
-    float* lq = lp.lq;
+    (void)stage_all(a, lay, lds_d);
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
@@ -347,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_pq_avg(const TraceArgs a, LdsLayout 
         qv[1] = qvec[3 * j + 1];
         qv[2] = qvec[3 * j + 2];
     }
-    out[j] = quad_average<KIND>(a, lq, q[j], qv);
+    out[j] = quad_average<KIND>(a, a.quad_nodes, q[j], qv);
 }
 
 // ------------------------------------------------------------------ Schulz tables (FP64)
@@ -873,6 +872,8 @@ int validate(const sans_params* p)
     if (!(p->poly >= 0.0 && p->poly <= 1.0)) return fail(SANS_E_INVALID_ARG, "poly must be in [0, 1]");
     if (p->poly > 0.0 && p->poly < 1e-4) return fail(SANS_E_INVALID_ARG, "poly must be 0 or >= 1e-4");
     if (p->poly_mask < 0 || p->poly_mask > 7) return fail(SANS_E_INVALID_ARG, "poly_mask must be in 0..7");
+    if (p->poly_kind != SANS_POLY_SCHULZ && p->poly_kind != SANS_POLY_GAUSSIAN)
+        return fail(SANS_E_UNSUPPORTED, "unknown poly_kind");
     if (p->table_size < 64 || p->table_size > 8192)
         return fail(SANS_E_INVALID_ARG, "table_size must be in 64..8192");
     for (int k = 0; k < 3; ++k) {
@@ -969,7 +970,7 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     a.inv_py = p->ny / p->det_h;
     a.nx = p->nx;
     a.ny = p->ny;
-    *mean_v = host::mean_volume(p->kind, p->size, p->shell, p->poly, p->poly_mask);
+    *mean_v = host::mean_volume(p->kind, p->size, p->shell, p->poly, p->poly_mask, p->poly_kind);
     const double dOmega = 2.0 * 3.141592653589793 * *omc;
     *wscale = 1e10 * dOmega * p->phi / *mean_v;
     a.wscale = *wscale;
@@ -1034,20 +1035,29 @@ int configure(sans_model_s* m, const sans_params* p)
     const bool need_size = p->mode == SANS_MODE_MC && a.poly_on;
     const bool need_norm = p->mode == SANS_MODE_MC && aniso && p->orient_kind == SANS_ORIENT_GAUSSIAN;
     const bool size_same = !first && old.table_size == p->table_size && old.poly == p->poly
-                           && !m->h_tab_size.empty();
+                           && old.poly_kind == p->poly_kind && !m->h_tab_size.empty();
     const bool norm_same = !first && old.table_size == p->table_size && !m->h_tab_norm.empty();
     if (need_size) {
         if (!size_same) {
             if (m->d_tab_size) HIP_TRY(hipFree(m->d_tab_size));
             m->d_tab_size = nullptr;
             HIP_TRY(hipMalloc(&m->d_tab_size, sizeof(double) * p->table_size));
-            const SchulzJob job = schulz_job(p->poly, 0);
-            int rc2 = build_schulz_tables(&job, 1, p->table_size, m->d_tab_size, nullptr);
-            if (rc2) return rc2;
-            HIP_TRY(hipStreamSynchronize(nullptr));
-            m->h_tab_size.assign(p->table_size, 0.0);
-            HIP_TRY(hipMemcpy(m->h_tab_size.data(), m->d_tab_size, sizeof(double) * p->table_size,
-                              hipMemcpyDeviceToHost));
+            if (p->poly_kind == SANS_POLY_GAUSSIAN) {
+                // closed-form quantile: built on the host
+                m->h_tab_size.resize(p->table_size);
+                for (int k = 0; k < p->table_size; ++k)
+                    m->h_tab_size[k] = host::positive_normal_quantile((k + 0.5) / p->table_size, p->poly);
+                HIP_TRY(hipMemcpy(m->d_tab_size, m->h_tab_size.data(), sizeof(double) * p->table_size,
+                                  hipMemcpyHostToDevice));
+            } else {
+                const SchulzJob job = schulz_job(p->poly, 0);
+                int rc2 = build_schulz_tables(&job, 1, p->table_size, m->d_tab_size, nullptr);
+                if (rc2) return rc2;
+                HIP_TRY(hipStreamSynchronize(nullptr));
+                m->h_tab_size.assign(p->table_size, 0.0);
+                HIP_TRY(hipMemcpy(m->h_tab_size.data(), m->d_tab_size, sizeof(double) * p->table_size,
+                                  hipMemcpyDeviceToHost));
+            }
         }
         a.tab_size = m->d_tab_size;
     }
@@ -1078,14 +1088,18 @@ int configure(sans_model_s* m, const sans_params* p)
             ny = n;
             ys.assign(n, 0.0);
             wy.assign(n, 0.0);
-            const double lo = std::max(0.0, 1.0 - 6.0 * p->poly), hi = 1.0 + 8.0 * p->poly;
+            const bool gauss = p->poly_kind == SANS_POLY_GAUSSIAN;
+            const double lo = std::max(0.0, 1.0 - 6.0 * p->poly), hi = 1.0 + (gauss ? 6.0 : 8.0) * p->poly;
             const double aa = 1.0 / (p->poly * p->poly);
             const double lnorm = aa * std::log(aa) - std::lgamma(aa);
             double tot = 0.0;
             for (int j = 0; j < n; ++j) {
                 ys[j] = lo + 0.5 * (hi - lo) * (gx[j] + 1.0);
                 const double y = ys[j];
-                const double pdf = y > 0.0 ? std::exp(lnorm + (aa - 1.0) * std::log(y) - aa * y) : 0.0;
+                const double d = (y - 1.0) / p->poly;
+                const double pdf = y <= 0.0 ? 0.0
+                                 : gauss  ? std::exp(-0.5 * d * d)
+                                          : std::exp(lnorm + (aa - 1.0) * std::log(y) - aa * y);
                 wy[j] = gw[j] * pdf;
                 tot += wy[j];
             }
@@ -1149,7 +1163,7 @@ LdsLayout layout(const sans_model_s* m, bool hist)
     l.tab_norm = off;
     if (a.tab_norm) off += a.M;
     l.quad = off;
-    l.quad_floats = (m->p.mode != SANS_MODE_MC) ? kQuadArrays * a.quad_n + 2 * a.quad_ny : 0;
+    l.quad_floats = 0;  // the quadrature nodes are read from global memory (uniform)
     off += (l.quad_floats + 1) / 2;
     l.total = off;
     return l;
@@ -1170,6 +1184,10 @@ int choose_tally(const sans_model_s* m, bool extras)
     int t = m->p.tally;
     // the optional sum-of-squares and count outputs use the atomic path
     if (extras) return t == SANS_TALLY_XCD ? SANS_TALLY_XCD : SANS_TALLY_GLOBAL;
+    // the exact average spends thousands of operations per tallied neutron:
+    // plain atomics cost nothing there, and the workgroup histogram's LDS
+    // would halve the waves per SIMD
+    if (t == SANS_TALLY_AUTO && m->p.mode == SANS_MODE_QUAD) t = SANS_TALLY_GLOBAL;
     if (t == SANS_TALLY_AUTO) t = hist_fits(m) ? SANS_TALLY_LDS : SANS_TALLY_BINNED;
     if (t == SANS_TALLY_LDS && !hist_fits(m)) t = SANS_TALLY_BINNED;
     if (t == SANS_TALLY_BINNED) {
@@ -1225,6 +1243,8 @@ int launch_fill(double* p, size_t n, hipStream_t s)
 bool surrogate_inputs(const sans_model_s* m, SurConst& sc)
 {
     const sans_params& p = m->p;
+    // the networks are trained on Schulz size distributions only
+    if (p.poly > 0.0 && p.poly_kind != SANS_POLY_SCHULZ) return false;
     const double x[4] = {0.0, std::log(p.size[1] / p.size[0]), std::log(p.size[2] / p.size[0]), p.poly};
     float u[4];
     for (int k = 1; k < 4; ++k) {
@@ -1872,8 +1892,12 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
     std::vector<SchulzJob> jobs;
     int rc;
     if ((rc = ensure(c.d_exps, c.exps_cap, (size_t)n_exp))) return rc;
-    size_t ntab = 0;
-    for (int e = 0; e < n_exp; ++e) ntab += p[e].poly > 0.0;
+    size_t ntab = 0, n_schulz = 0;
+    for (int e = 0; e < n_exp; ++e) {
+        ntab += p[e].poly > 0.0;
+        n_schulz += p[e].poly > 0.0 && p[e].poly_kind == SANS_POLY_SCHULZ;
+    }
+    std::vector<double> host_tabs;
     if ((rc = ensure(c.d_tables, c.tables_cap, std::max<size_t>(1, ntab * M)))) return rc;
     if ((rc = ensure(c.d_jobs, c.jobs_cap, std::max<size_t>(1, ntab)))) return rc;
     if (!c.d_counter && hipMalloc(&c.d_counter, sizeof(unsigned)) != hipSuccess) {
@@ -1896,12 +1920,19 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
         exps[e].seed_lo = (uint32_t)seeds[e];
         exps[e].seed_hi = (uint32_t)(seeds[e] >> 32);
         exps[e].exp_id = (uint32_t)e;
-        if (p[e].poly > 0.0) {
+        if (p[e].poly > 0.0 && p[e].poly_kind == SANS_POLY_GAUSSIAN) {
+            // closed-form quantiles, built on the host (after the Schulz slots)
+            exps[e].tab_size = c.d_tables + (n_schulz + host_tabs.size() / M) * (size_t)M;
+            for (int k = 0; k < M; ++k) host_tabs.push_back(host::positive_normal_quantile((k + 0.5) / M, p[e].poly));
+        } else if (p[e].poly > 0.0) {
             exps[e].tab_size = c.d_tables + jobs.size() * (size_t)M;
             jobs.push_back(schulz_job(p[e].poly, (unsigned long long)(jobs.size() * (size_t)M)));
         }
         if (p[e].kind >= 2 && p[e].orient_kind == SANS_ORIENT_GAUSSIAN) exps[e].tab_norm = c.d_norm;
     }
+    if (!host_tabs.empty())
+        HIP_TRY(hipMemcpyAsync(c.d_tables + n_schulz * (size_t)M, host_tabs.data(), sizeof(double) * host_tabs.size(),
+                               hipMemcpyHostToDevice, s));
     if ((rc = set_lds_limit((const void*)k_batch, lds))) return rc;
 
     // tile size: tuning cache, else autotune (when a cache path is given), else default

@@ -26,6 +26,7 @@ import numpy as np
 KINDS = ("sphere", "core_shell", "cylinder", "ellipsoid", "parallelepiped")
 ORIENT_KINDS = ("fixed", "gaussian", "isotropic", "uniform_angles")
 MODES = ("mc", "quad", "surrogate")
+POLY_KINDS = ("schulz", "gaussian")
 
 DEG = math.pi / 180.0
 
@@ -45,7 +46,7 @@ SAMPLE_DEFAULTS = dict(
     kind="sphere", mode="mc",
     size=(50.0, 0.0, 0.0), shell=0.0, sld=(1e-6, 0.0, 0.0),
     phi=0.01, sq_phi=0.0, sq_radius=0.0,
-    poly=0.0, poly_mask=1,
+    poly=0.0, poly_mask=1, poly_kind="schulz",
     orient_kind="fixed", orient_mean=(0.0, 0.0, 0.0), orient_sigma=(0.0, 0.0, 0.0),
     table_size=4096, quad_n=76,
 )

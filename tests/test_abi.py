@@ -85,3 +85,11 @@ def test_null_arguments(S):
     assert S.lib.sans_trace(None, 10, 1, None, None, None) == S.SANS_E_INVALID_ARG
     assert S.lib.sans_debug_philox(1, 0, 10, 2, 0, None, None) == S.SANS_E_INVALID_ARG
     assert S.lib.sans_model_destroy(None) == S.SANS_OK
+
+
+def test_unknown_poly_kind_rejected_without_gpu(S):
+    from paper_2501_06054_amd import workloads as W
+    sp = S.to_params(W.params(poly=0.1))
+    sp.poly_kind = 7
+    h = C.c_void_p()
+    assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED

@@ -115,3 +115,23 @@ def test_batch_rejects_mismatched_detectors(S):
     out = torch.empty((2, 128, 128), dtype=torch.float64, device="cuda")
     with pytest.raises(S.SansError):
         S.sans_trace_batch([exps[0]["params"], p1], [10, 10], [1, 1], out)
+
+
+def test_batch_gaussian_sizes(S):
+    """Experiments with the paper's Gaussian size rule mixed with Schulz ones:
+    each equals its plain trace, and two match the oracle."""
+    exps = _small_batch(n_exp=12, n_lo=2e5, n_hi=6e5)
+    for e in range(0, 12, 2):
+        exps[e]["params"] = dict(exps[e]["params"], poly_kind="gaussian",
+                                 poly=max(exps[e]["params"]["poly"], 0.05))
+    got = _run_batch(S, exps)
+    for e, x in enumerate(exps):
+        m = S.Model(x["params"])
+        ref = m.trace(x["n"], x["seed"], exp_id=e).cpu().numpy()
+        m.close()
+        assert np.allclose(got[e], ref, rtol=1e-9, atol=0), e
+    for e in (0, 2):
+        x = exps[e]
+        ref = oracle.trace(x["params"], x["n"], x["seed"], exp_id=e, nthreads=NTHREADS)
+        assert np.array_equal(got[e] != 0, ref != 0), e
+        assert abs(got[e].sum() - ref.sum()) <= 1e-6 * abs(ref.sum()), e

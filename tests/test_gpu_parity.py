@@ -90,6 +90,17 @@ def test_tables_match_oracle(S, poly):
     m.close()
 
 
+@pytest.mark.parametrize("poly", [0.05, 0.2, 0.35])
+def test_gaussian_size_table_matches_oracle(S, poly):
+    p = W.params(kind="sphere", size=(50, 0, 0), poly=poly, poly_kind="gaussian")
+    m = S.Model(p)
+    M = p["table_size"]
+    ts = S.sans_debug_table(m.handle, 1, M)
+    ref = oracle.table_truncnorm(M, poly)
+    assert np.allclose(ts, ref, rtol=1e-12, atol=1e-14)
+    m.close()
+
+
 # ------------------------------------------------------------------ per neutron
 
 PER_NEUTRON = {
@@ -115,6 +126,15 @@ PER_NEUTRON = {
                                 sq_radius=50.0, phi=0.2), 2003),
     "quad_fixed_cylinder": (W.params(kind="cylinder", mode="quad", size=(20, 400, 0), poly=0.1,
                                      orient_mean=(math.pi / 2, 0, 0)), 2003),
+    # the paper's own size rule: Gaussian, positive sizes only
+    "gauss_coreshell_py": (W.params(kind="core_shell", size=(40, 0, 0), shell=10,
+                                    sld=(1e-6, 3e-6, 6.3e-6), poly=0.3, poly_kind="gaussian",
+                                    sq_phi=0.2, sq_radius=50.0, phi=0.2, nx=256, ny=256), 50021),
+    "gauss_cylinder_uniform_angles": (W.params(kind="cylinder", size=(30, 200, 0), poly=0.35,
+                                               poly_kind="gaussian", poly_mask=3,
+                                               orient_kind="uniform_angles"), 30011),
+    "quad_gauss_sphere": (W.params(kind="sphere", mode="quad", size=(50, 0, 0), poly=0.25,
+                                   poly_kind="gaussian"), 2003),
 }
 
 
@@ -137,7 +157,7 @@ def test_per_neutron_parity(S, name, first):
 # ------------------------------------------------------------------ detectors
 
 DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellipsoid",
-             "iso_parallelepiped", "poly_ellipsoid_py"]
+             "iso_parallelepiped", "poly_ellipsoid_py", "gauss_coreshell_py"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)

@@ -446,3 +446,47 @@ def test_experiment_id_changes_stream(orc):
     a = orc.trace_debug(p, 100, 1, exp_id=0)[1]
     b = orc.trace_debug(p, 100, 1, exp_id=1)[1]
     assert not np.allclose(a, b)
+
+
+# ------------------------------------------------------------------ the paper's Gaussian sizes
+
+@pytest.mark.parametrize("p", [0.05, 0.2, 0.35, 0.6])
+def test_truncnorm_quantile_vs_library(orc, p):
+    """N(1, p^2) kept where positive (Methods, Polydispersity, Eq. (8)):
+    the quantile against SciPy's truncated normal."""
+    from scipy import stats
+    tn = stats.truncnorm(-1.0 / p, np.inf, loc=1.0, scale=p)
+    for u in (1e-6, 1e-3, 0.1, 0.37, 0.5, 0.9, 0.999, 1 - 1e-6):
+        assert abs(orc.truncnorm_quantile(u, p) - tn.ppf(u)) <= 1e-11 * max(1.0, tn.ppf(u))
+
+
+@pytest.mark.parametrize("p", [0.1, 0.3, 0.6])
+def test_truncnorm_moments_vs_library(orc, p):
+    from scipy import stats
+    tn = stats.truncnorm(-1.0 / p, np.inf, loc=1.0, scale=p)
+    par = W.params(kind="sphere", size=(50, 0, 0), poly=p, poly_kind="gaussian")
+    for k in range(0, 7):
+        assert orc.size_moment(par, k) == pytest.approx(tn.moment(k), rel=1e-10)
+
+
+def test_gaussian_sizes_by_table_follow_the_distribution(orc):
+    """Sizes drawn by the table lookup at uniform u follow the truncated
+    normal (KS distance) and are all positive."""
+    from scipy import stats
+    p = 0.45
+    knots = orc.table_truncnorm(4096, p)
+    u = (np.arange(200_000) + 0.5) / 200_000
+    y = np.array([orc.table_lookup(knots, ui) for ui in u[::10]])
+    assert y.min() > 0.0
+    d = stats.kstest(y, stats.truncnorm(-1.0 / p, np.inf, loc=1.0, scale=p).cdf).statistic
+    assert d < 2e-3
+
+
+def test_gaussian_poly_mc_matches_quadrature(orc):
+    """Monte Carlo over Gaussian sizes against the size quadrature of the
+    same distribution (sphere, total detected intensity)."""
+    base = dict(kind="sphere", size=(60.0, 0, 0), poly=0.3, poly_kind="gaussian", nx=64, ny=64)
+    n = 400_000
+    mc = orc.trace(W.params(**base), n, 17, nthreads=8).sum()
+    qd = orc.trace(W.params(mode="quad", **base), n, 17, nthreads=8).sum()
+    assert abs(mc / qd - 1.0) < 4e-3
