@@ -42,9 +42,11 @@
  * in Angstrom; angles in radians.                                          */
 typedef struct {
     int32_t kind;          /* 0 sphere, 1 core-shell sphere, 2 cylinder,
-                              3 triaxial ellipsoid, 4 parallelepiped        */
+                              3 triaxial ellipsoid, 4 parallelepiped,
+                              5 barbell, 6 capped cylinder                  */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
-    double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C */
+    double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
+                              barbell / capped cylinder: R, L, cap radius r >= R */
     double shell;          /* core-shell shell thickness                     */
     double sld[3];         /* particle (core), shell, solvent                */
     double phi;            /* particle volume fraction, n = phi/<V>          */
@@ -360,9 +362,70 @@ double orc_py_sq(double q, double radius, double phi)
 
 static double vol_sphere(double r) { return 4.0 / 3.0 * ORC_PI * r * r * r; }
 
-/* Amplitude for one set of (possibly scaled) sizes. */
+/* Gauss-Legendre nodes on [-1, 1] for the caps' integral, computed once per
+ * order (under a lock; read-only afterwards). */
+static pthread_mutex_t g_cap_lock = PTHREAD_MUTEX_INITIALIZER;
+static double g_cap_x[ORC_MAX_QUAD + 1][ORC_MAX_QUAD], g_cap_w[ORC_MAX_QUAD + 1][ORC_MAX_QUAD];
+static int g_cap_ready[ORC_MAX_QUAD + 1];
+
+void orc_gauss_legendre(int32_t n, double* x, double* w);
+
+static void cap_nodes(int n, const double** x, const double** w)
+{
+    pthread_mutex_lock(&g_cap_lock);
+    if (!g_cap_ready[n]) {
+        orc_gauss_legendre(n, g_cap_x[n], g_cap_w[n]);
+        g_cap_ready[n] = 1;
+    }
+    pthread_mutex_unlock(&g_cap_lock);
+    *x = g_cap_x[n];
+    *w = g_cap_w[n];
+}
+
+/* Bodies of revolution about C made of a cylinder (radius R, length L,
+ * |z| <= L/2) and two spherical caps of radius r >= R that meet the end
+ * faces in the circle of radius R (Tables I-II, group A: Barbell, Capped
+ * cylinder).  The cap sphere's centre sits at z_c = L/2 + h: h = +sqrt(r^2 -
+ * R^2) beyond the end face (barbell: the cap is most of a sphere) or h =
+ * -sqrt(r^2 - R^2) inside the cylinder (capped cylinder: a dome).  The
+ * amplitude is the Fourier transform of the body: slicing it into discs of
+ * radius rho(z) normal to C, a disc contributes pi rho^2 2J1(Q_AB rho)/(Q_AB
+ * rho) e^{i Q_C z}; the cylinder gives pi R^2 L sinc(Q_C L/2) 2J1(Q_AB
+ * R)/(Q_AB R), and the caps (z = z_c + r t, rho = r sqrt(1 - t^2), t from
+ * t0 = -h/r to 1, both ends adding the complex conjugates)
+ *   2 pi r^3 int_{t0}^{1} cos(Q_C (z_c + r t)) (1 - t^2)
+ *                         2J1(Q_AB r sqrt(1-t^2))/(Q_AB r sqrt(1-t^2)) dt,
+ * here by n-point Gauss-Legendre.  Volume: pi R^2 L + 2 pi (r^3 (1 - t0)
+ * - r^3 (1 - t0^3)/3). */
+static double caps_amplitude(const double s[3], int barbell, double qab, double qc, int n)
+{
+    double R = s[0], L = s[1], r = s[2];
+    double h = sqrt(r * r - R * R) * (barbell ? 1.0 : -1.0);
+    double zc = 0.5 * L + h, t0 = -h / r;
+    const double *gx, *gw;
+    cap_nodes(n, &gx, &gw);
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double t = 0.5 * (1.0 - t0) * gx[i] + 0.5 * (1.0 + t0);
+        double rho = r * sqrt(1.0 - t * t);
+        sum += gw[i] * cos(qc * (zc + r * t)) * (1.0 - t * t) * orc_lambda1(qab * rho);
+    }
+    return 2.0 * ORC_PI * r * r * r * 0.5 * (1.0 - t0) * sum;
+}
+
+static double caps_volume(const double s[3], int barbell)
+{
+    double R = s[0], r = s[2];
+    double h = sqrt(r * r - R * R) * (barbell ? 1.0 : -1.0);
+    double t0 = -h / r;
+    /* pi r^3 int_{t0}^{1} (1 - t^2) dt, twice */
+    return 2.0 * ORC_PI * r * r * r * ((1.0 - t0) - (1.0 - t0 * t0 * t0) / 3.0);
+}
+
+/* Amplitude for one set of (possibly scaled) sizes; cap_n is the
+ * Gauss-Legendre order of the caps' integral (barbell, capped cylinder). */
 static double amplitude(int kind, const double s[3], double shell, const double sld[3],
-                        double q, double qa, double qb, double qc)
+                        double q, double qa, double qb, double qc, int cap_n)
 {
     double drho = sld[0] - sld[2];
     switch (kind) {
@@ -390,6 +453,14 @@ static double amplitude(int kind, const double s[3], double shell, const double 
         double a = s[0], b = s[1], c = s[2];
         return drho * a * b * c * orc_sinc(0.5 * qa * a) * orc_sinc(0.5 * qb * b)
              * orc_sinc(0.5 * qc * c);
+    }
+    case 5:   /* barbell */
+    case 6: { /* capped cylinder */
+        double r = s[0], len = s[1];
+        double qab2 = q * q - qc * qc;
+        double qab = qab2 > 0.0 ? sqrt(qab2) : 0.0;
+        double cyl = ORC_PI * r * r * len * orc_sinc(0.5 * qc * len) * orc_lambda1(qab * r);
+        return drho * (cyl + caps_amplitude(s, kind == 5, qab, qc, cap_n));
     }
     }
     return 0.0;
@@ -457,6 +528,10 @@ double orc_mean_volume(const orc_params* p)
         return 4.0 / 3.0 * ORC_PI * s[0] * s[1] * s[2] * size_moment(p, b0 + b1 + b2);
     case 4:
         return s[0] * s[1] * s[2] * size_moment(p, b0 + b1 + b2);
+    case 5:
+    case 6: /* all three sizes scale together (or none): V(y) = V(1) y^3 */
+        return (ORC_PI * s[0] * s[0] * s[1] + caps_volume(s, p->kind == 5))
+             * size_moment(p, p->poly_mask == 7 ? 3 : 0);
     }
     return 0.0;
 }
@@ -571,7 +646,7 @@ static double pq_avg_nodes(const orc_params* p, double q, const double qvec[3],
     int aniso = (p->kind >= 2);
     int iso = aniso && p->orient_kind == 2;
     /* a spheroid (a = b, scaled alike) needs only the angle to its C axis */
-    int one_axis = (p->kind == 2)
+    int one_axis = (p->kind == 2 || p->kind == 5 || p->kind == 6)
                 || (p->kind == 3 && p->size[0] == p->size[1]
                     && (p->poly_mask & 1) == (p->poly_mask >> 1 & 1));
     double A[3], B[3], C[3];
@@ -583,20 +658,20 @@ static double pq_avg_nodes(const orc_params* p, double q, const double qvec[3],
         scaled_sizes(p, ys[j], s);
         double avg = 0.0;
         if (!aniso) {
-            double f = amplitude(p->kind, s, p->shell, p->sld, q, 0.0, 0.0, 0.0);
+            double f = amplitude(p->kind, s, p->shell, p->sld, q, 0.0, 0.0, 0.0, p->quad_n);
             avg = f * f;
         } else if (!iso) {
             double qa = qvec[0] * A[0] + qvec[1] * A[1] + qvec[2] * A[2];
             double qb = qvec[0] * B[0] + qvec[1] * B[1] + qvec[2] * B[2];
             double qc = qvec[0] * C[0] + qvec[1] * C[1] + qvec[2] * C[2];
-            double f = amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc);
+            double f = amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc, p->quad_n);
             avg = f * f;
         } else if (one_axis) {
             for (int i = 0; i < n; ++i) {
                 double mu = 0.5 * (gx[i] + 1.0);
                 double st = sqrt(1.0 - mu * mu);
                 /* A-B plane direction is irrelevant for a symmetric particle */
-                double f = amplitude(p->kind, s, p->shell, p->sld, q, q * st, 0.0, q * mu);
+                double f = amplitude(p->kind, s, p->shell, p->sld, q, q * st, 0.0, q * mu, p->quad_n);
                 avg += 0.5 * gw[i] * f * f;
             }
         } else {
@@ -606,7 +681,7 @@ static double pq_avg_nodes(const orc_params* p, double q, const double qvec[3],
                 for (int k = 0; k < n; ++k) {
                     double beta = 0.25 * ORC_PI * (gx[k] + 1.0);
                     double qa = q * st * cos(beta), qb = q * st * sin(beta), qc = q * mu;
-                    double f = amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc);
+                    double f = amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc, p->quad_n);
                     avg += 0.25 * gw[i] * gw[k] * f * f;
                 }
             }
@@ -635,7 +710,7 @@ double orc_amplitude(const orc_params* p, double q, const double qvec[3], double
     double qa = qvec[0] * A[0] + qvec[1] * A[1] + qvec[2] * A[2];
     double qb = qvec[0] * B[0] + qvec[1] * B[1] + qvec[2] * B[2];
     double qc = qvec[0] * C[0] + qvec[1] * C[1] + qvec[2] * C[2];
-    return amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc);
+    return amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc, p->quad_n);
 }
 
 /* ------------------------------------------------------------------------ */

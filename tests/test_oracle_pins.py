@@ -490,3 +490,82 @@ def test_gaussian_poly_mc_matches_quadrature(orc):
     mc = orc.trace(W.params(**base), n, 17, nthreads=8).sum()
     qd = orc.trace(W.params(mode="quad", **base), n, 17, nthreads=8).sum()
     assert abs(mc / qd - 1.0) < 4e-3
+
+
+# ------------------------------------------------------------------ barbell / capped cylinder
+
+def _capped_body_ft(R, L, r, barbell, qab, qc, nz=600, nr=48, nphi=48):
+    """The Fourier transform int cos(Q.x) dV of the body, by a product
+    Gauss rule over (z, rho, phi) of its points: cylinder |z| <= L/2, rho <=
+    R, plus the parts of the cap spheres (radius r, centres at +-(L/2 + h),
+    h = +-sqrt(r^2 - R^2)) beyond the end faces."""
+    h = math.sqrt(r * r - R * R) * (1.0 if barbell else -1.0)
+    zc = 0.5 * L + h
+    zmax = zc + r
+    gz, wz = np.polynomial.legendre.leggauss(nz)
+    gr, wr = np.polynomial.legendre.leggauss(nr)
+    gp, wp = np.polynomial.legendre.leggauss(nphi)
+    total = 0.0
+    # the body is symmetric in z: twice the z >= 0 half; split at L/2
+    for a, b in ((0.0, 0.5 * L), (0.5 * L, zmax)):
+        if b <= a:
+            continue
+        z = 0.5 * (b - a) * gz + 0.5 * (b + a)
+        w_z = 0.5 * (b - a) * wz
+        rho_max = np.where(z <= 0.5 * L, R, np.sqrt(np.maximum(r * r - (z - zc) ** 2, 0.0)))
+        rho = 0.5 * rho_max[:, None] * (gr[None, :] + 1.0)
+        w_rho = 0.5 * rho_max[:, None] * wr[None, :]
+        phi = math.pi * (gp + 1.0)
+        w_phi = math.pi * wp
+        arg = qc * z[:, None, None] + qab * rho[:, :, None] * np.cos(phi)[None, None, :]
+        integrand = np.cos(arg) * rho[:, :, None]
+        total += 2.0 * np.einsum("i,ij,k,ijk->", w_z, w_rho, w_phi, integrand)
+    return total
+
+
+@pytest.mark.parametrize("kind", ["barbell", "capped_cylinder"])
+@pytest.mark.parametrize("qab,qc", [(0.0, 0.0), (0.03, 0.0), (0.0, 0.02), (0.025, 0.04), (0.06, 0.013)])
+def test_capped_body_amplitude_is_the_fourier_transform(orc, kind, qab, qc):
+    R, L, r = 20.0, 120.0, 32.0
+    p = W.params(kind=kind, size=(R, L, r), sld=(1.0, 0.0, 0.0), quad_n=76)
+    q = math.hypot(qab, qc)
+    # axis C along z (angles 0): Q = (qab, 0, qc)
+    got = orc.amplitude(p, q, (qab, 0.0, qc), 1.0, (0.0, 0.0, 0.0))
+    ref = _capped_body_ft(R, L, r, kind == "barbell", qab, qc)
+    assert got == pytest.approx(ref, rel=1e-8, abs=1e-9 * abs(ref) + 1e-6)
+
+
+@pytest.mark.parametrize("kind", ["barbell", "capped_cylinder"])
+def test_capped_body_volume(orc, kind):
+    """F(0) = drho V with V = cylinder + two spherical caps of height r +- h."""
+    R, L, r = 20.0, 120.0, 32.0
+    p = W.params(kind=kind, size=(R, L, r), sld=(1.0, 0.0, 0.0))
+    h = math.sqrt(r * r - R * R) * (1.0 if kind == "barbell" else -1.0)
+    hc = r + h
+    v = math.pi * R * R * L + 2.0 * math.pi * hc * hc * (3.0 * r - hc) / 3.0
+    assert orc.amplitude(p, 0.0, (0.0, 0.0, 0.0)) == pytest.approx(v, rel=1e-12)
+    assert orc.mean_volume(p) == pytest.approx(v, rel=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["barbell", "capped_cylinder"])
+def test_capped_body_reduces_to_sphere(orc, kind):
+    """Hemispherical caps (r = R) on a cylinder of zero length: a sphere."""
+    R = 35.0
+    p = W.params(kind=kind, size=(R, 0.0 + 1e-12, R), sld=(1.0, 0.0, 0.0))
+    v = 4.0 / 3.0 * math.pi * R ** 3
+    for qv in ((0.02, 0.0, 0.0), (0.0, 0.0, 0.05), (0.03, 0.01, 0.04)):
+        q = math.sqrt(sum(c * c for c in qv))
+        got = orc.amplitude(p, q, qv, 1.0, (0.3, 1.1, 0.0))
+        assert got == pytest.approx(v * orc.sph(q * R), rel=1e-10, abs=1e-9 * v)
+
+
+def test_capped_body_quadrature_converged(orc):
+    """The caps' Gauss-Legendre order 76 agrees with order 200."""
+    for kind in ("barbell", "capped_cylinder"):
+        a = W.params(kind=kind, size=(20.0, 400.0, 40.0), quad_n=76)
+        b = dict(a, quad_n=200)
+        for qv in ((0.05, 0.0, 0.01), (0.01, 0.02, 0.05)):
+            q = math.sqrt(sum(c * c for c in qv))
+            fa = orc.amplitude(a, q, qv, 1.0, (0.4, 0.2, 0.0))
+            fb = orc.amplitude(b, q, qv, 1.0, (0.4, 0.2, 0.0))
+            assert fa == pytest.approx(fb, rel=1e-12, abs=1e-12 * abs(fb) + 1e-15)
