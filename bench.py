@@ -68,6 +68,8 @@ STEP = {
     "core_shell_F":  ((29,  0,  0, 10, 0, 0), 44),
     "cylinder_F":    ((24,  0,  0, 13, 0, 1), 39),  # Q_AB (sqrt), sinc and 2 J1(x)/x series
     "ellipsoid_F":   ((15,  0,  0, 15, 0, 1), 25),  # |(aQ_A, bQ_B, cQ_C)| (sqrt), series
+    "caps_phase":    ((16,  6,  0,  8, 0, 0), 26),  # cap centre phase: FP64 reduction, sincos polynomials
+    "cap_node":      ((37,  6,  0,  0, 0, 0), 58),  # per cap node: sincos of B t, angle sum, 2 J1(x)/x series
     "py_sq":         ((15,  0,  0,  0, 1, 0), 25),  # A10: series in x^2, 1/(1 + 24 phi G/x)
     "weight":        ((3,   0,  0,  2, 0, 0), 3),   # A11
     "detector":      ((0,   5,  0, 23, 0, 1), 0),   # A12: plane crossing (quotient), pixel
@@ -89,6 +91,10 @@ PATHS = {
                          + ["qvec"] + ["orient_angle"] * 2 + ["project_c", "cylinder_F"],
     "oriented_ellipsoid": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
                           + ["qvec"] + ["orient_angle"] * 3 + ["project_abc", "ellipsoid_F"],
+    # barbell: the cylinder's amplitude plus the caps' 76-node integral
+    "oriented_barbell": COMMON + ["philox_block"] * 3 + ["uniform"] * 10
+                        + ["qvec"] + ["orient_angle"] * 2 + ["project_c", "cylinder_F", "caps_phase"]
+                        + ["cap_node"] * 76,
 }
 # Exact-average paths, per quadrature node (76 x 76 = 5776 nodes per neutron),
 # all FP32:
@@ -98,8 +104,14 @@ PATHS = {
 #   node the C sinc and its weight: 12 ops, 20 flops;
 #   spheroid (mu x size nodes): q mu, q st, 3 mul, 2 fma, sqrt (trans32), the
 #   3 j1(x)/x series (9), square and weighted sum: 18 ops + 1 trans32, 35 flops.
-QUAD_NODE = {"quad_parallelepiped": ((15, 0, 0, 0, 0, 0), 24), "quad_spheroid": ((18, 0, 0, 0, 1, 0), 35)}
-QUAD_MU = {"quad_parallelepiped": ((12, 0, 0, 0, 0, 0), 20), "quad_spheroid": ((0, 0, 0, 0, 0, 0), 0)}
+#   capped cylinder (mu x cap nodes): per cap node as in the Monte Carlo path
+#   (cap_node); per mu node Q_AB (sqrt), the cylinder's sinc and 2 J1(x)/x
+#   series, the FP32-reduced cap-centre phase, F^2 and its weight: 57 ops +
+#   6 int + 1 trans32, 83 flops.
+QUAD_NODE = {"quad_parallelepiped": ((15, 0, 0, 0, 0, 0), 24), "quad_spheroid": ((18, 0, 0, 0, 1, 0), 35),
+             "quad_capped_cylinder": STEP["cap_node"]}
+QUAD_MU = {"quad_parallelepiped": ((12, 0, 0, 0, 0, 0), 20), "quad_spheroid": ((0, 0, 0, 0, 0, 0), 0),
+           "quad_capped_cylinder": ((57, 6, 0, 0, 1, 0), 83)}
 QUAD_NODES = 76 * 76
 QUAD_BASE = COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["qvec"]
 

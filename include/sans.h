@@ -66,7 +66,12 @@ typedef enum {
     SANS_CORE_SHELL_SPHERE = 1,/* size[0] = core R, shell = thickness            */
     SANS_CYLINDER = 2,         /* size[0] = R, size[1] = L; axis = particle C    */
     SANS_ELLIPSOID = 3,        /* semi-axes size[0..2] along particle A, B, C    */
-    SANS_PARALLELEPIPED = 4    /* edges size[0..2] along particle A, B, C        */
+    SANS_PARALLELEPIPED = 4,   /* edges size[0..2] along particle A, B, C        */
+    SANS_BARBELL = 5,          /* cylinder R = size[0], L = size[1] (axis C) with
+                                  two spherical end caps of radius r = size[2]
+                                  >= R whose centres lie outside the cylinder   */
+    SANS_CAPPED_CYLINDER = 6   /* the same cylinder and cap radius, cap centres
+                                  inside the cylinder (lens-shaped end caps)    */
 } sans_kind;
 
 /* How the particle size and orientation enter the weight. */
@@ -162,7 +167,10 @@ typedef struct {
     double sample_w, sample_h, sample_d;
     double det_w, det_h, det_z;
     int32_t nx, ny;
-    int32_t quad_n;          /* Gauss-Legendre order of SANS_MODE_QUAD (<= 256) */
+    int32_t quad_n;          /* Gauss-Legendre order of SANS_MODE_QUAD (<= 256);
+                                also the order of the end-cap integral of
+                                SANS_BARBELL / SANS_CAPPED_CYLINDER in every
+                                mode                                           */
     int32_t tally;           /* sans_tally                                     */
     int32_t poly_kind;       /* sans_poly                                      */
     int32_t reserved;        /* 0                                              */
@@ -174,9 +182,11 @@ typedef struct sans_model_s* sans_model_t;
  * quantiles at (k + 1/2)/M, FP64, staged in LDS by the kernels)
  * and the model constants.  *out receives an opaque handle owning its device
  * buffers.  Errors: SANS_E_INVALID_ARG (null pointers, wrong abi_version, a
- * size <= 0, negative widths or spreads, phi or sq_phi outside [0, 1) / [0,
- * 0.6), nx*ny outside 1..2^26), SANS_E_UNSUPPORTED (unknown kind/mode/orient,
- * QUAD with Gaussian or uniform-angle orientation), SANS_E_NOMEM, SANS_E_HIP. */
+ * size <= 0, a cap radius below the cylinder radius, negative widths or
+ * spreads, phi or sq_phi outside [0, 1) / [0, 0.6), nx*ny outside 1..2^26),
+ * SANS_E_UNSUPPORTED (unknown kind/mode/orient, QUAD with Gaussian or
+ * uniform-angle orientation, a capped body with poly > 0 and poly_mask != 7),
+ * SANS_E_NOMEM, SANS_E_HIP. */
 int sans_model_create(const sans_params* p, sans_model_t* out);
 
 /* Frees the handle and its device buffers (after synchronising its streams'

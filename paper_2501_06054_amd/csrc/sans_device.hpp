@@ -92,6 +92,14 @@ struct TraceArgs {
     const float* quad_nodes;      // mu[n] wmu[n] cb[n] sb[n] wb[n] st[n] y[ny] wy[ny] (global)
     float fsize[3], fshell;       // FP32 copies for the quadrature loop
     float fA[3], fB[3], fC[3];    // fixed-orientation particle axes (FP32)
+    // barbell / capped cylinder: the caps' Gauss-Legendre rule at y = 1, FP32
+    // [3][cap_n] in global memory: t in [t0, 1], s = r sqrt(1 - t^2) (A) and
+    // w = 2 pi r^3 (1 - t^2) w_t (1 - t0)/2 (A^3); the cap centre's distance
+    // z_c from the particle centre and the cap radius r (A)
+    int32_t cap_n;
+    const float* cap_nodes;
+    double cap_zc, cap_r;
+    float fcap_zc, fcap_r;
     // run
     uint64_t first, n;
     uint32_t seed_lo, seed_hi, exp_id;
@@ -419,7 +427,37 @@ __device__ __forceinline__ void project(const Trig3& g, const double qv[3], doub
 }
 
 // ---------------------------------------------------------------- models
-enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParallelepiped = 4 };
+enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParallelepiped = 4,
+              kBarbell = 5, kCappedCylinder = 6 };
+
+// Bodies of revolution about C: cylinder, barbell, capped cylinder (only the
+// axis projection Q.C and Q_AB enter, the third angle does not).
+template <int KIND>
+constexpr bool kOneAxis = KIND == kCylinder || KIND == kBarbell || KIND == kCappedCylinder;
+
+// The caps' part of the barbell / capped-cylinder amplitude (Tables I-II,
+// group A), in FP32: sum_i w_i cos(P + B t_i) 2J1(X s_i)/(X s_i) over the
+// Gauss-Legendre nodes t_i of the cap integral at unit size, where P = y Q_C
+// z_c is the phase of the cap centre (its sine and cosine come in as sP, cP,
+// reduced by the caller), B = y Q_C r and X = y Q_AB.  Splitting the phase
+// keeps the per-node argument B t_i within |y Q_C r|, so it needs no
+// precision beyond FP32.  The caller multiplies by y^3.  The node arrays are
+// read with uniform indices (scalar loads).
+__device__ __forceinline__ float caps_sum(const TraceArgs& a, float sP, float cP, float B, float X)
+{
+    const float* __restrict__ tn = a.cap_nodes;
+    const float* __restrict__ sn = a.cap_nodes + a.cap_n;
+    const float* __restrict__ wn = a.cap_nodes + 2 * a.cap_n;
+    float sum = 0.0f;
+#pragma unroll 4
+    for (int i = 0; i < a.cap_n; ++i) {
+        float sv, cv;
+        sincos_f(B * tn[i], sv, cv);
+        const float c = __builtin_fmaf(cP, cv, -(sP * sv));
+        sum = __builtin_fmaf(wn[i] * c, lambda1_f(X * sn[i]), sum);
+    }
+    return sum;
+}
 
 // F of one drawn particle (MC mode).  y scales the sizes selected by the
 // polydispersity mask; q, qa, qb, qc are |Q| and its projections (FP64).
@@ -448,6 +486,16 @@ __device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, doub
         const double xa = qa * s[0], xb = qb * s[1], xc = qc * s[2];
         const double x = sqrt(xa * xa + xb * xb + xc * xc);
         return a.contrast * k43pi * (float)s[0] * (float)s[1] * (float)s[2] * sph3j_d(x);
+    } else if constexpr (KIND == kBarbell || KIND == kCappedCylinder) {
+        const double qab = sqrt(fmax(__builtin_fma(q, q, -qc * qc), 0.0));
+        const float r = (float)s[0], len = (float)s[1];
+        const float cyl = (float)kPi * r * r * len * sinc_d(0.5 * qc * s[1]) * lambda1_f((float)(qab * s[0]));
+        const double qcy = qc * y;
+        float sP, cP;
+        sincos_phase(qcy * a.cap_zc, sP, cP);
+        const float yf = (float)y;
+        const float caps = caps_sum(a, sP, cP, (float)(qcy * a.cap_r), (float)(qab * y));
+        return a.contrast * __builtin_fmaf(yf * yf * yf, caps, cyl);
     } else {
         return a.contrast * (float)s[0] * (float)s[1] * (float)s[2] * sinc_d(0.5 * qa * s[0])
              * sinc_d(0.5 * qb * s[1]) * sinc_d(0.5 * qc * s[2]);
@@ -457,7 +505,7 @@ __device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, doub
 // F in FP32 throughout (quadrature loops; sizes s and projections FP32).
 template <int KIND>
 __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3], float q, float qa,
-                                             float qb, float qc)
+                                             float qb, float qc, float y)
 {
     constexpr float k43pi = (float)(4.0 / 3.0 * kPi);
     if constexpr (KIND == kSphere) {
@@ -475,6 +523,15 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
         const float xa = qa * s[0], xb = qb * s[1], xc = qc * s[2];
         const float x = sqrtf(xa * xa + xb * xb + xc * xc);
         return a.contrast * k43pi * s[0] * s[1] * s[2] * sph3j_f(x);
+    } else if constexpr (KIND == kBarbell || KIND == kCappedCylinder) {
+        const float r = s[0], len = s[1];
+        const float qab = sqrtf(fmaxf(__builtin_fmaf(q, q, -qc * qc), 0.0f));
+        const float cyl = (float)kPi * r * r * len * sinc_f(0.5f * qc * len) * lambda1_f(qab * r);
+        const float qcy = qc * y;
+        float sP, cP;
+        sincos_f(qcy * a.fcap_zc, sP, cP);
+        const float caps = caps_sum(a, sP, cP, qcy * a.fcap_r, qab * y);
+        return a.contrast * __builtin_fmaf(y * y * y, caps, cyl);
     } else {
         return a.contrast * s[0] * s[1] * s[2] * sinc_f(0.5f * qa * s[0]) * sinc_f(0.5f * qb * s[1])
              * sinc_f(0.5f * qc * s[2]);
@@ -522,12 +579,12 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
         for (int c = 0; c < 3; ++c) s[c] = (a.poly_mask >> c & 1) ? a.fsize[c] * y : a.fsize[c];
         float avg = 0.0f;
         if (a.quad_dims == 0) {
-            const float f = amplitude_f<KIND>(a, s, q, qa0, qb0, qc0);
+            const float f = amplitude_f<KIND>(a, s, q, qa0, qb0, qc0, y);
             avg = i0 == 0 ? f * f : 0.0f;
         } else if (a.quad_dims == 1) {
 #pragma unroll 4
             for (int i = i0; i < n; i += istep) {
-                const float f = amplitude_f<KIND>(a, s, q, q * stt[i], 0.0f, q * mu[i]);
+                const float f = amplitude_f<KIND>(a, s, q, q * stt[i], 0.0f, q * mu[i], y);
                 avg = __builtin_fmaf(wmu[i], f * f, avg);
             }
         } else if constexpr (KIND == kParallelepiped) {
@@ -551,7 +608,7 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
                 const float qc = q * mu[i];
                 float inner = 0.0f;
                 for (int l = 0; l < n; ++l) {
-                    const float f = amplitude_f<KIND>(a, s, q, qst * cb[l], qst * sb[l], qc);
+                    const float f = amplitude_f<KIND>(a, s, q, qst * cb[l], qst * sb[l], qc, y);
                     inner = __builtin_fmaf(wb[l], f * f, inner);
                 }
                 avg = __builtin_fmaf(wmu[i], inner, avg);
@@ -665,7 +722,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
                               a.ang_sigma[0] * table_lerp(tab_norm, a.M, u64(r2.y)), g.st, g.ct);
                     rotate_by(a.ang_sin[1], a.ang_cos[1],
                               a.ang_sigma[1] * table_lerp(tab_norm, a.M, u64(r2.z)), g.sp, g.cp);
-                    if constexpr (KIND != kCylinder)
+                    if constexpr (!kOneAxis<KIND>)
                         rotate_by(a.ang_sin[2], a.ang_cos[2],
                                   a.ang_sigma[2] * table_lerp(tab_norm, a.M, u64(r2.w)), g.ss, g.cs);
                 } else if (a.orient_kind == 2) {
@@ -673,17 +730,17 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
                     g.ct = __builtin_fma(2.0, u64(r2.y), -1.0);
                     g.st = sqrt(fmax(__builtin_fma(-g.ct, g.ct, 1.0), 0.0));
                     sincospi(2.0 * u64(r2.z), &g.sp, &g.cp);
-                    if constexpr (KIND != kCylinder) sincospi(2.0 * u64(r2.w), &g.ss, &g.cs);
+                    if constexpr (!kOneAxis<KIND>) sincospi(2.0 * u64(r2.w), &g.ss, &g.cs);
                 } else if (a.orient_kind == 3) {
                     // the literal rule: theta uniform in [0, pi)
                     sincospi(u64(r2.y), &g.st, &g.ct);
                     sincospi(2.0 * u64(r2.z), &g.sp, &g.cp);
-                    if constexpr (KIND != kCylinder) sincospi(2.0 * u64(r2.w), &g.ss, &g.cs);
+                    if constexpr (!kOneAxis<KIND>) sincospi(2.0 * u64(r2.w), &g.ss, &g.cs);
                 }
             }
         }
         double qa = 0.0, qb = 0.0, qc = 0.0;
-        if constexpr (KIND >= kCylinder) project<KIND != kCylinder>(g, qvd, qa, qb, qc);
+        if constexpr (KIND >= kCylinder) project<!kOneAxis<KIND>>(g, qvd, qa, qb, qc);
         const float f = amplitude_mc<KIND>(a, y, qd, qa, qb, qc);
         f2 = f * f;
     } else if constexpr (MODE == 1) {

@@ -203,8 +203,42 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
     case 4:
         return size[0] * size[1] * size[2]
              * size_moment(poly_kind, poly, (b0 ? 1 : 0) + (b1 ? 1 : 0) + (b2 ? 1 : 0));
+    case 5:
+    case 6: {
+        // every length scales with y (mask 7), so V(y) = y^3 V(1)
+        double zc, t0, vcaps;
+        cap_geometry(kind == 5, size[0], size[1], size[2], &zc, &t0, &vcaps);
+        const double v1 = kPiH * size[0] * size[0] * size[1] + vcaps;
+        return v1 * size_moment(poly_kind, poly, mask == 7 ? 3 : 0);
+    }
     }
     return 0.0;
+}
+
+void cap_geometry(bool barbell, double R, double L, double r, double* zc, double* t0, double* vcaps)
+{
+    // the cap sphere cuts the cylinder's end circle at height h = +-sqrt(r^2 - R^2)
+    // below its centre: outside the cylinder for the barbell, inside otherwise
+    const double h = std::sqrt(std::max(r * r - R * R, 0.0)) * (barbell ? 1.0 : -1.0);
+    *zc = 0.5 * L + h;
+    *t0 = -h / r;
+    // each cap: pi r^3 times the integral of (1 - t^2) over [t0, 1]
+    *vcaps = 2.0 * kPiH * r * r * r * ((1.0 - *t0) - (1.0 - *t0 * *t0 * *t0) / 3.0);
+}
+
+void cap_rule(bool barbell, double R, double L, double r, int n, float* out)
+{
+    double zc, t0, vcaps;
+    cap_geometry(barbell, R, L, r, &zc, &t0, &vcaps);
+    std::vector<double> gx(n), gw(n);
+    gauss_legendre(n, gx.data(), gw.data());
+    for (int i = 0; i < n; ++i) {
+        const double t = 0.5 * (1.0 - t0) * gx[i] + 0.5 * (1.0 + t0);
+        const double one_t2 = std::max(1.0 - t * t, 0.0);
+        out[i] = (float)t;
+        out[n + i] = (float)(r * std::sqrt(one_t2));
+        out[2 * n + i] = (float)(2.0 * kPiH * r * r * r * one_t2 * gw[i] * 0.5 * (1.0 - t0));
+    }
 }
 
 }  // namespace host

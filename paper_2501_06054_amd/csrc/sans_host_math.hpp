@@ -12,6 +12,14 @@ double positive_normal_quantile(double u, double p);
 double positive_normal_moment(double p, int k);
 double size_moment(int poly_kind, double p, int k);
 double mean_volume(int kind, const double size[3], double shell, double poly, int mask, int poly_kind);
+// End caps of a barbell (barbell = true) or capped cylinder of radius R,
+// length L, cap radius r >= R: the cap centre's distance from the particle
+// centre, the lowest point t0 (in units of r, from the cap centre) where a cap
+// meets the cylinder, and the volume of the two caps beyond the cylinder.
+void cap_geometry(bool barbell, double R, double L, double r, double* zc, double* t0, double* vcaps);
+// The caps' n-point Gauss-Legendre rule at unit size as FP32 arrays [3][n]:
+// t_i in [t0, 1], r sqrt(1 - t_i^2) and 2 pi r^3 (1 - t_i^2) w_i (1 - t0)/2.
+void cap_rule(bool barbell, double R, double L, double r, int n, float* out);
 
 }  // namespace host
 }  // namespace sans

@@ -498,7 +498,9 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 1: batch_tile<1>(a, tl.first, tl.count, hist, tab); break;
         case 2: batch_tile<2>(a, tl.first, tl.count, hist, tab); break;
         case 3: batch_tile<3>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<4>(a, tl.first, tl.count, hist, tab); break;
+        case 4: batch_tile<4>(a, tl.first, tl.count, hist, tab); break;
+        case 5: batch_tile<5>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<6>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -645,7 +647,7 @@ __global__ __launch_bounds__(kBlock) void k_pq_dataset(const TraceArgs a, const 
             for (int i = 0; i < nq; ++i) {
                 const float m = mu[i];
                 const float st = sqrtf(fmaxf(1.0f - m * m, 0.0f));
-                const float f = amplitude_f<KIND>(a, s, q, q * st, 0.0f, q * m);
+                const float f = amplitude_f<KIND>(a, s, q, q * st, 0.0f, q * m, (float)y);
                 avg = __builtin_fmaf(wmu[i], f * f, avg);
             }
         } else {
@@ -655,13 +657,13 @@ __global__ __launch_bounds__(kBlock) void k_pq_dataset(const TraceArgs a, const 
                 const float qc = q * m;
                 float inner = 0.0f;
                 for (int l = 0; l < nq; ++l) {
-                    const float f = amplitude_f<KIND>(a, s, q, qst * cb[l], qst * sb[l], qc);
+                    const float f = amplitude_f<KIND>(a, s, q, qst * cb[l], qst * sb[l], qc, (float)y);
                     inner = __builtin_fmaf(wb[l], f * f, inner);
                 }
                 avg = __builtin_fmaf(wmu[i], inner, avg);
             }
         }
-        const float f0 = amplitude_f<KIND>(a, s, 0.0f, 0.0f, 0.0f, 0.0f);
+        const float f0 = amplitude_f<KIND>(a, s, 0.0f, 0.0f, 0.0f, 0.0f, (float)y);
         num += wy * (double)avg;
         den += wy * (double)f0 * (double)f0;
         wsum += wy;
@@ -736,6 +738,8 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(2)
         SANS_CASE(3)
         SANS_CASE(4)
+        SANS_CASE(5)
+        SANS_CASE(6)
     }
 #undef SANS_CASE
     return nullptr;
@@ -755,6 +759,8 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(2)
         SANS_CASE(3)
         SANS_CASE(4)
+        SANS_CASE(5)
+        SANS_CASE(6)
     }
 #undef SANS_CASE
     return nullptr;
@@ -771,6 +777,8 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(2)
         SANS_CASE(3)
         SANS_CASE(4)
+        SANS_CASE(5)
+        SANS_CASE(6)
     }
 #undef SANS_CASE
     return nullptr;
@@ -787,6 +795,8 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(2)
         SANS_CASE(3)
         SANS_CASE(4)
+        SANS_CASE(5)
+        SANS_CASE(6)
     }
 #undef SANS_CASE
     return nullptr;
@@ -800,6 +810,8 @@ PqFn pick_pq(int kind)
     case 2: return k_pq_avg<2>;
     case 3: return k_pq_avg<3>;
     case 4: return k_pq_avg<4>;
+    case 5: return k_pq_avg<5>;
+    case 6: return k_pq_avg<6>;
     }
     return nullptr;
 }
@@ -816,6 +828,7 @@ struct sans_model_s {
     double* d_tab_size = nullptr;
     double* d_tab_norm = nullptr;
     float* d_quad = nullptr;
+    float* d_caps = nullptr;   // end-cap rule [3][quad_n] (barbell, capped cylinder)
     double* d_replicas = nullptr;
     size_t replica_pix = 0;
     // tally workspaces (grown on demand, freed with the model)
@@ -846,7 +859,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 4) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 6) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -862,6 +875,13 @@ int validate(const sans_params* p)
     const int nsize = p->kind <= 1 ? 1 : (p->kind == 2 ? 2 : 3);
     for (int k = 0; k < nsize; ++k)
         if (!(p->size[k] > 0.0) || !finite(p->size[k])) return fail(SANS_E_INVALID_ARG, "size must be > 0");
+    if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
+        if (!(p->size[2] >= p->size[0]))
+            return fail(SANS_E_INVALID_ARG, "cap radius size[2] must be >= the cylinder radius size[0]");
+        if (p->poly > 0.0 && p->poly_mask != 7)
+            return fail(SANS_E_UNSUPPORTED, "barbell / capped cylinder: poly_mask must be 7 (all sizes)");
+        if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
+    }
     if (p->kind == 1 && !(p->shell >= 0.0 && finite(p->shell)))
         return fail(SANS_E_INVALID_ARG, "shell must be >= 0");
     for (int k = 0; k < 3; ++k)
@@ -983,6 +1003,15 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     }
     a.shell = p->shell;
     a.fshell = (float)p->shell;
+    if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
+        double zc, t0, vcaps;
+        host::cap_geometry(p->kind == SANS_BARBELL, p->size[0], p->size[1], p->size[2], &zc, &t0, &vcaps);
+        a.cap_n = p->quad_n;
+        a.cap_zc = zc;
+        a.cap_r = p->size[2];
+        a.fcap_zc = (float)zc;
+        a.fcap_r = (float)p->size[2];
+    }
     {
         // fixed-orientation axes for the quadrature path: A = R x, B = R y, C = R z
         const double st = a.ang_sin[0], ct = a.ang_cos[0], sp = a.ang_sin[1], cp = a.ang_cos[1],
@@ -1075,6 +1104,17 @@ int configure(sans_model_s* m, const sans_params* p)
         a.tab_norm = m->d_tab_norm;
     }
 
+    // the end caps' rule (every mode)
+    if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
+        std::vector<float> rule(3 * (size_t)p->quad_n);
+        host::cap_rule(p->kind == SANS_BARBELL, p->size[0], p->size[1], p->size[2], p->quad_n, rule.data());
+        if (m->d_caps) HIP_TRY(hipFree(m->d_caps));
+        m->d_caps = nullptr;
+        HIP_TRY(hipMalloc(&m->d_caps, sizeof(float) * rule.size()));
+        HIP_TRY(hipMemcpy(m->d_caps, rule.data(), sizeof(float) * rule.size(), hipMemcpyHostToDevice));
+        a.cap_nodes = m->d_caps;
+    }
+
     // quadrature nodes: mu in [0, 1], beta in [0, pi/2], size y in
     // [max(0, 1 - 6p), 1 + 8p] with Schulz weights normalised to sum 1
     // (also the exact fallback and normalisation of the surrogate mode)
@@ -1109,7 +1149,8 @@ int configure(sans_model_s* m, const sans_params* p)
         if (aniso && p->orient_kind == SANS_ORIENT_ISOTROPIC) {
             const bool spheroid = p->kind == 3 && p->size[0] == p->size[1]
                                   && ((p->poly_mask & 1) != 0) == ((p->poly_mask & 2) != 0);
-            dims = (p->kind == 2 || spheroid) ? 1 : 2;
+            dims = (p->kind == SANS_CYLINDER || p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER
+                    || spheroid) ? 1 : 2;
         }
         a.quad_n = n;
         a.quad_ny = ny;
@@ -1353,6 +1394,7 @@ int sans_model_destroy(sans_model_t m)
     if (m->d_tab_size) (void)hipFree(m->d_tab_size);
     if (m->d_tab_norm) (void)hipFree(m->d_tab_norm);
     if (m->d_quad) (void)hipFree(m->d_quad);
+    if (m->d_caps) (void)hipFree(m->d_caps);
     if (m->d_replicas) (void)hipFree(m->d_replicas);
     if (m->d_partial) (void)hipFree(m->d_partial);
     if (m->d_buckets) (void)hipFree(m->d_buckets);
@@ -1710,6 +1752,8 @@ struct BatchCache {
     size_t tables_cap = 0;
     double* d_norm = nullptr;
     int norm_M = 0;
+    float* d_caps = nullptr;   // end-cap rules of the capped bodies, one after another
+    size_t caps_cap = 0;
     unsigned* d_counter = nullptr;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -1729,6 +1773,7 @@ struct BatchCache {
         if (d_jobs) (void)hipFree(d_jobs);
         if (d_tables) (void)hipFree(d_tables);
         if (d_norm) (void)hipFree(d_norm);
+        if (d_caps) (void)hipFree(d_caps);
         if (d_counter) (void)hipFree(d_counter);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         d_exps = nullptr;
@@ -1736,9 +1781,10 @@ struct BatchCache {
         d_jobs = nullptr;
         d_tables = nullptr;
         d_norm = nullptr;
+        d_caps = nullptr;
         d_counter = nullptr;
         cap_stream = nullptr;
-        exps_cap = tiles_cap = jobs_cap = tables_cap = 0;
+        exps_cap = tiles_cap = jobs_cap = tables_cap = caps_cap = 0;
         norm_M = 0;
     }
 };
@@ -1898,6 +1944,11 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
         n_schulz += p[e].poly > 0.0 && p[e].poly_kind == SANS_POLY_SCHULZ;
     }
     std::vector<double> host_tabs;
+    std::vector<float> host_caps;
+    size_t ncaps = 0;
+    for (int e = 0; e < n_exp; ++e)
+        if (p[e].kind == SANS_BARBELL || p[e].kind == SANS_CAPPED_CYLINDER) ncaps += 3 * (size_t)p[e].quad_n;
+    if ((rc = ensure(c.d_caps, c.caps_cap, std::max<size_t>(1, ncaps)))) return rc;
     if ((rc = ensure(c.d_tables, c.tables_cap, std::max<size_t>(1, ntab * M)))) return rc;
     if ((rc = ensure(c.d_jobs, c.jobs_cap, std::max<size_t>(1, ntab)))) return rc;
     if (!c.d_counter && hipMalloc(&c.d_counter, sizeof(unsigned)) != hipSuccess) {
@@ -1929,7 +1980,16 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
             jobs.push_back(schulz_job(p[e].poly, (unsigned long long)(jobs.size() * (size_t)M)));
         }
         if (p[e].kind >= 2 && p[e].orient_kind == SANS_ORIENT_GAUSSIAN) exps[e].tab_norm = c.d_norm;
+        if (p[e].kind == SANS_BARBELL || p[e].kind == SANS_CAPPED_CYLINDER) {
+            const size_t off = host_caps.size();
+            host_caps.resize(off + 3 * (size_t)p[e].quad_n);
+            host::cap_rule(p[e].kind == SANS_BARBELL, p[e].size[0], p[e].size[1], p[e].size[2], p[e].quad_n,
+                           host_caps.data() + off);
+            exps[e].cap_nodes = c.d_caps + off;
+        }
     }
+    if (!host_caps.empty())
+        HIP_TRY(hipMemcpyAsync(c.d_caps, host_caps.data(), sizeof(float) * host_caps.size(), hipMemcpyHostToDevice, s));
     if (!host_tabs.empty())
         HIP_TRY(hipMemcpyAsync(c.d_tables + n_schulz * (size_t)M, host_tabs.data(), sizeof(double) * host_tabs.size(),
                                hipMemcpyHostToDevice, s));

@@ -24,6 +24,9 @@ import math
 import numpy as np
 
 KINDS = ("sphere", "core_shell", "cylinder", "ellipsoid", "parallelepiped")
+#: bodies of revolution with spherical caps (Tables I-II, group A); not in the
+#: batched experiment generator
+CAPPED_KINDS = ("barbell", "capped_cylinder")
 ORIENT_KINDS = ("fixed", "gaussian", "isotropic", "uniform_angles")
 MODES = ("mc", "quad", "surrogate")
 POLY_KINDS = ("schulz", "gaussian")
@@ -124,6 +127,26 @@ def quad_spheroid() -> dict:
                               orient_kind="isotropic"))
 
 
+def oriented_barbell() -> dict:
+    """Barbells: cylinder R = 20 A, L = 400 A with spherical end caps of radius
+    40 A, axis along x with Gaussian angular spread 10 deg; the caps' integral
+    by 76-point Gauss-Legendre per neutron; 256x256 detector, 1e8 neutrons."""
+    return dict(name="oriented_barbell", n=10**8, seed=8, exp_id=0,
+                params=params(kind="barbell", size=(20.0, 400.0, 40.0), sld=(1e-6, 0, 0),
+                              phi=0.01, orient_kind="gaussian",
+                              orient_mean=(90 * DEG, 0.0, 0.0),
+                              orient_sigma=(10 * DEG, 10 * DEG, 0.0), nx=256, ny=256))
+
+
+def quad_capped_cylinder() -> dict:
+    """Isotropically oriented capped cylinders (R = 20 A, L = 400 A, cap
+    radius 25 A), exact average over 76 orientation nodes, each with the
+    76-node cap integral, 128x128 detector, 1e7 neutrons."""
+    return dict(name="quad_capped_cylinder", n=10**7, seed=9, exp_id=0,
+                params=params(kind="capped_cylinder", mode="quad", size=(20.0, 400.0, 25.0),
+                              sld=(1e-6, 0, 0), phi=0.01, orient_kind="isotropic"))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -131,6 +154,8 @@ WORKLOADS = {
     "oriented_ellipsoid": oriented_ellipsoid,
     "quad_parallelepiped": quad_parallelepiped,
     "quad_spheroid": quad_spheroid,
+    "oriented_barbell": oriented_barbell,
+    "quad_capped_cylinder": quad_capped_cylinder,
 }
 
 

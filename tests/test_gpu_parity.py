@@ -44,7 +44,13 @@ def check_weights(w_gpu, w_orc, where=""):
                            f"{np.max(np.abs(w_gpu - w_orc) / np.maximum(tol, 1e-300)):.3g} x tol")
 
 
-def check_detector(d_gpu, d_orc, where=""):
+def check_detector(d_gpu, d_orc, where="", count=None, w_max=None):
+    """Same hit pixels, total within 1e-6 and every hit pixel within 1e-4
+    relative.  With count (the oracle's hits per pixel) and w_max (the
+    largest single weight), a pixel may instead deviate by the sum of the
+    per-neutron bar over its neutrons, 1e-4 |pixel| + 1e-5 w_max count: the
+    bar for models whose amplitude has zeros inside the Q range (the capped
+    bodies), where a sparse pixel can be one neutron near a zero of F."""
     d_gpu = np.asarray(d_gpu)
     assert d_gpu.shape == d_orc.shape
     # same set of hit pixels
@@ -52,8 +58,27 @@ def check_detector(d_gpu, d_orc, where=""):
     tot_g, tot_o = d_gpu.sum(), d_orc.sum()
     assert abs(tot_g - tot_o) <= 1e-6 * abs(tot_o), f"{where}: total {tot_g} vs {tot_o}"
     nz = d_orc != 0
-    rel = np.abs(d_gpu[nz] - d_orc[nz]) / np.abs(d_orc[nz])
-    assert rel.max() <= 1e-4 if rel.size else True, f"{where}: worst pixel rel {rel.max():.3g}"
+    err = np.abs(d_gpu[nz] - d_orc[nz])
+    if count is None:
+        rel = err / np.abs(d_orc[nz])
+        assert rel.max() <= 1e-4 if rel.size else True, f"{where}: worst pixel rel {rel.max():.3g}"
+    else:
+        tol = 1e-4 * np.abs(d_orc[nz]) + 1e-5 * w_max * count[nz].astype(np.float64)
+        assert (err <= tol).all(), f"{where}: worst pixel {np.max(err / tol):.3g} x the summed bar"
+
+
+# models judged pixel by pixel with the summed per-neutron bar
+SUMMED_BAR = ("barbell", "capped_cylinder")
+
+
+def oracle_detector(p, n, seed, first=0):
+    """The oracle's detector, plus (count, w_max) for the summed bar where the
+    model needs it (w_max over the first 100003 of these neutrons)."""
+    if p["kind"] not in SUMMED_BAR:
+        return oracle.trace(p, n, seed, first=first, nthreads=NTHREADS), {}
+    ref, _, cnt = oracle.trace(p, n, seed, first=first, nthreads=NTHREADS, with_count=True)
+    _, w, _ = oracle.trace_debug(p, min(n, 100003), seed, first=first)
+    return ref, dict(count=cnt, w_max=float(np.max(np.abs(w))))
 
 
 # ------------------------------------------------------------------ streams
@@ -135,6 +160,19 @@ PER_NEUTRON = {
                                                orient_kind="uniform_angles"), 30011),
     "quad_gauss_sphere": (W.params(kind="sphere", mode="quad", size=(50, 0, 0), poly=0.25,
                                    poly_kind="gaussian"), 2003),
+    # bodies with spherical end caps (the caps' integral by quad_n-point
+    # Gauss-Legendre in every mode; 23 nodes leave a ragged unrolled tail)
+    "oriented_barbell": (W.workload("oriented_barbell")["params"], 30011),
+    "poly_capped_cylinder_iso": (W.params(kind="capped_cylinder", size=(20, 200, 25), poly=0.15,
+                                          poly_mask=7, orient_kind="isotropic"), 30011),
+    "gauss_barbell_uniform_angles": (W.params(kind="barbell", size=(30, 150, 45), poly=0.1,
+                                              poly_kind="gaussian", poly_mask=7, quad_n=23,
+                                              orient_kind="uniform_angles"), 30011),
+    "hemisphere_capped_cylinder": (W.params(kind="capped_cylinder", size=(40, 120, 40),
+                                            orient_mean=(math.pi / 4, math.pi / 6, 0)), 30011),
+    "quad_capped_cylinder": (dict(W.workload("quad_capped_cylinder")["params"]), 601),
+    "quad_poly_barbell_fixed": (W.params(kind="barbell", mode="quad", size=(20, 400, 40), poly=0.1,
+                                         poly_mask=7, orient_mean=(math.pi / 2, 0, 0)), 2003),
 }
 
 
@@ -157,7 +195,8 @@ def test_per_neutron_parity(S, name, first):
 # ------------------------------------------------------------------ detectors
 
 DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellipsoid",
-             "iso_parallelepiped", "poly_ellipsoid_py", "gauss_coreshell_py"]
+             "iso_parallelepiped", "poly_ellipsoid_py", "gauss_coreshell_py", "oriented_barbell",
+             "poly_capped_cylinder_iso"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -169,24 +208,25 @@ def test_detector_parity(S, name, tally):
     m = S.Model(p, tally=tally)
     det = m.trace(n, seed)
     torch.cuda.synchronize()
-    ref = oracle.trace(p, n, seed, nthreads=NTHREADS)
-    check_detector(det.cpu().numpy(), ref, f"{name}/{tally}")
+    ref, bar = oracle_detector(p, n, seed)
+    check_detector(det.cpu().numpy(), ref, f"{name}/{tally}", **bar)
     m.close()
 
 
-def test_quad_detector_parity(S):
-    p = W.workload("quad_parallelepiped")["params"]
+@pytest.mark.parametrize("name", ["quad_parallelepiped", "quad_capped_cylinder"])
+def test_quad_detector_parity(S, name):
+    p = W.workload(name)["params"]
     n, seed = 6007, 6
     m = S.Model(p)
     det = m.trace(n, seed)
     torch.cuda.synchronize()
-    ref = oracle.trace(p, n, seed, nthreads=NTHREADS)
-    check_detector(det.cpu().numpy(), ref, "quad_parallelepiped")
+    ref, bar = oracle_detector(p, n, seed)
+    check_detector(det.cpu().numpy(), ref, name, **bar)
     m.close()
 
 
 def test_pq_avg_matches_oracle(S):
-    for name in ("quad_parallelepiped", "quad_spheroid", "quad_coreshell"):
+    for name in ("quad_parallelepiped", "quad_spheroid", "quad_coreshell", "quad_capped_cylinder"):
         p, _ = PER_NEUTRON[name]
         m = S.Model(p)
         qs = np.concatenate([np.linspace(0.0, 0.06, 61), np.geomspace(1e-4, 0.3, 40)])
@@ -285,9 +325,9 @@ def test_full_size_coreshell(S):
     m.close()
 
 
-@pytest.mark.parametrize("name", ["oriented_cylinder", "oriented_ellipsoid"])
+@pytest.mark.parametrize("name", ["oriented_cylinder", "oriented_ellipsoid", "oriented_barbell"])
 def test_full_size_sampled(S, name):
-    """1e9-neutron workloads: the full run equals the sum of its chunks, and
+    """1e9- and 1e8-neutron workloads: the full run equals the sum of its chunks, and
     windows spread over the whole index range match the oracle neutron by
     neutron."""
     wl = W.workload(name)
@@ -311,8 +351,8 @@ def test_full_size_sampled(S, name):
     # the first 5e6 neutrons as a whole detector
     head = m.trace(5_000_000, seed)
     torch.cuda.synchronize()
-    ref = oracle.trace(p, 5_000_000, seed, nthreads=NTHREADS)
-    check_detector(head.cpu().numpy(), ref, f"{name} head")
+    ref, bar = oracle_detector(p, 5_000_000, seed)
+    check_detector(head.cpu().numpy(), ref, f"{name} head", **bar)
     m.close()
 
 
