@@ -19,7 +19,7 @@ SRC = os.path.join(HERE, "sans_oracle.c")
 SO = os.path.join(HERE, "liboracle.so")
 
 KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelepiped": 4,
-        "barbell": 5, "capped_cylinder": 6}
+        "barbell": 5, "capped_cylinder": 6, "hollow_prism": 7}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
 POLY_KIND = {"schulz": 0, "gaussian": 1}

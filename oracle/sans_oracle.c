@@ -43,11 +43,13 @@
 typedef struct {
     int32_t kind;          /* 0 sphere, 1 core-shell sphere, 2 cylinder,
                               3 triaxial ellipsoid, 4 parallelepiped,
-                              5 barbell, 6 capped cylinder                  */
+                              5 barbell, 6 capped cylinder,
+                              7 hollow rectangular prism with thin walls    */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
-                              barbell / capped cylinder: R, L, cap radius r >= R */
-    double shell;          /* core-shell shell thickness                     */
+                              barbell / capped cylinder: R, L, cap radius r >= R |
+                              hollow prism: outer edges A, B, C            */
+    double shell;          /* core-shell shell thickness; hollow prism wall   */
     double sld[3];         /* particle (core), shell, solvent                */
     double phi;            /* particle volume fraction, n = phi/<V>          */
     double sq_phi;         /* hard-sphere volume fraction; 0 -> S = 1        */
@@ -462,6 +464,17 @@ static double amplitude(int kind, const double s[3], double shell, const double 
         double cyl = ORC_PI * r * r * len * orc_sinc(0.5 * qc * len) * orc_lambda1(qab * r);
         return drho * (cyl + caps_amplitude(s, kind == 5, qab, qc, cap_n));
     }
+    case 7: { /* hollow rectangular prism, walls of thickness shell -> 0: the
+                 six faces as sheets of areal density shell; the two faces
+                 normal to an axis sit at +-half that edge, so their sum is
+                 2 cos(half phase) times the face's own transform (the two
+                 in-plane sinc factors times its area) */
+        double a = s[0], b = s[1], c = s[2];
+        double xa = 0.5 * qa * a, xb = 0.5 * qb * b, xc = 0.5 * qc * c;
+        double sa = orc_sinc(xa), sb = orc_sinc(xb), sc = orc_sinc(xc);
+        return drho * 2.0 * shell
+             * (b * c * cos(xa) * sb * sc + a * c * sa * cos(xb) * sc + a * b * sa * sb * cos(xc));
+    }
     }
     return 0.0;
 }
@@ -532,6 +545,10 @@ double orc_mean_volume(const orc_params* p)
     case 6: /* all three sizes scale together (or none): V(y) = V(1) y^3 */
         return (ORC_PI * s[0] * s[0] * s[1] + caps_volume(s, p->kind == 5))
              * size_moment(p, p->poly_mask == 7 ? 3 : 0);
+    case 7: /* wall volume: thickness times the surface 2 (AB + BC + AC) */
+        return 2.0 * p->shell
+             * (s[0] * s[1] * size_moment(p, b0 + b1) + s[1] * s[2] * size_moment(p, b1 + b2)
+                + s[0] * s[2] * size_moment(p, b0 + b2));
     }
     return 0.0;
 }

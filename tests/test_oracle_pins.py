@@ -255,10 +255,15 @@ def test_parallelepiped_cube_rod(orc):
     ("ellipsoid", (20, 40, 120), (20**2 + 40**2 + 120**2) / 5),
     ("parallelepiped", (20, 40, 120), (20**2 + 40**2 + 120**2) / 12),
     ("ellipsoid", (20, 20, 60), (2 * 20**2 + 60**2) / 5),
+    # thin walls: the faces' mean squared distance, weighted by face area
+    ("hollow_prism", (20, 40, 120),
+     (2 * 40 * 120 * (20**2 / 4 + 40**2 / 12 + 120**2 / 12)
+      + 2 * 20 * 120 * (40**2 / 4 + 20**2 / 12 + 120**2 / 12)
+      + 2 * 20 * 40 * (120**2 / 4 + 20**2 / 12 + 40**2 / 12)) / (2 * (20 * 40 + 40 * 120 + 20 * 120))),
 ])
 def test_isotropic_average_guinier(orc, kind, size, rg2):
     # the orientation-averaged form factor obeys P = 1 - q^2 Rg^2 / 3 + O(q^4)
-    p = W.params(kind=kind, size=size, orient_kind="isotropic", mode="quad")
+    p = W.params(kind=kind, size=size, shell=1.0, orient_kind="isotropic", mode="quad")
     v2 = (orc.amplitude(p, 0.0, (0, 0, 0))) ** 2
     q = 2e-4
     pbar = orc.pq_avg(p, q) / v2
@@ -401,11 +406,12 @@ def test_coreshell_total_intensity_unbiased(orc):
 
 @pytest.mark.parametrize("kind,size", [("cylinder", (20, 400, 0)),
                                        ("parallelepiped", (20, 40, 120)),
-                                       ("ellipsoid", (20, 40, 120))])
+                                       ("ellipsoid", (20, 40, 120)),
+                                       ("hollow_prism", (30, 50, 150))])
 def test_isotropic_mc_matches_quadrature(orc, kind, size):
     # Monte Carlo draws of an isotropic orientation (cos theta uniform) give
     # the same detector total as the exact orientation average
-    mc = W.params(kind=kind, size=size, orient_kind="isotropic", mode="mc")
+    mc = W.params(kind=kind, size=size, shell=2.0, orient_kind="isotropic", mode="mc")
     qd = dict(mc, mode="quad", quad_n=40)
     n = 200_000
     det, w2, _ = orc.trace(mc, n, 9, nthreads=8, with_w2=True, with_count=True)
@@ -569,3 +575,64 @@ def test_capped_body_quadrature_converged(orc):
             fa = orc.amplitude(a, q, qv, 1.0, (0.4, 0.2, 0.0))
             fb = orc.amplitude(b, q, qv, 1.0, (0.4, 0.2, 0.0))
             assert fa == pytest.approx(fb, rel=1e-12, abs=1e-12 * abs(fb) + 1e-15)
+
+
+# ------------------------------------------------------------------ hollow prism, thin walls
+
+def _thin_box_ft(a, b, c, qv, n=64):
+    """int cos(Q.x) dS over the six faces of the box [-a/2, a/2] x [-b/2, b/2]
+    x [-c/2, c/2], each face by an n x n product Gauss rule."""
+    g, w = np.polynomial.legendre.leggauss(n)
+    total = 0.0
+    half = (0.5 * a, 0.5 * b, 0.5 * c)
+    for k in range(3):                       # faces normal to axis k
+        i, j = [m for m in range(3) if m != k]
+        u = half[i] * g
+        v = half[j] * g
+        wu = half[i] * w
+        wv = half[j] * w
+        for sign in (-1.0, 1.0):
+            arg = (qv[k] * sign * half[k] + qv[i] * u[:, None] + qv[j] * v[None, :])
+            total += np.einsum("i,j,ij->", wu, wv, np.cos(arg))
+    return total
+
+
+@pytest.mark.parametrize("qv", [(0.0, 0.0, 0.0), (0.03, 0.0, 0.0), (0.0, 0.05, 0.0), (0.0, 0.0, 0.02),
+                                (0.021, -0.034, 0.047), (0.11, 0.07, -0.013)])
+def test_hollow_prism_amplitude_is_the_surface_transform(orc, qv):
+    a, b, c, t = 30.0, 50.0, 140.0, 1.5
+    p = W.params(kind="hollow_prism", size=(a, b, c), shell=t, sld=(1.0, 0.0, 0.0))
+    q = math.sqrt(sum(x * x for x in qv))
+    got = orc.amplitude(p, q, qv, 1.0, (0.0, 0.0, 0.0))     # A, B, C along x, y, z
+    ref = t * _thin_box_ft(a, b, c, qv)
+    assert got == pytest.approx(ref, rel=1e-10, abs=1e-10 * t * 2 * (a * b + b * c + a * c))
+
+
+def test_hollow_prism_is_the_thin_wall_limit_of_two_boxes(orc):
+    """(F_box(a, b, c) - F_box(a - 2t, b - 2t, c - 2t)) / t -> the thin-wall
+    amplitude per unit wall as t -> 0 (first order in t)."""
+    a, b, c = 30.0, 50.0, 140.0
+    hol = W.params(kind="hollow_prism", size=(a, b, c), shell=1.0, sld=(1.0, 0.0, 0.0))
+    for qv in ((0.02, 0.01, 0.03), (0.0, 0.07, -0.02), (0.05, -0.04, 0.01)):
+        q = math.sqrt(sum(x * x for x in qv))
+        ang = (0.7, 0.3, 1.9)
+        ref = orc.amplitude(hol, q, qv, 1.0, ang)
+        for t in (1e-3, 1e-4):
+            outer = W.params(kind="parallelepiped", size=(a, b, c), sld=(1.0, 0.0, 0.0))
+            inner = dict(outer, size=(a - 2 * t, b - 2 * t, c - 2 * t))
+            diff = (orc.amplitude(outer, q, qv, 1.0, ang) - orc.amplitude(inner, q, qv, 1.0, ang)) / t
+            assert diff == pytest.approx(ref, rel=50 * t / a, abs=1e-6 * a * c)
+
+
+def test_hollow_prism_volume(orc):
+    a, b, c, t = 30.0, 50.0, 140.0, 1.5
+    p = W.params(kind="hollow_prism", size=(a, b, c), shell=t, sld=(1.0, 0.0, 0.0))
+    v = 2 * t * (a * b + b * c + a * c)
+    assert orc.amplitude(p, 0.0, (0.0, 0.0, 0.0)) == pytest.approx(v, rel=1e-13)
+    assert orc.mean_volume(p) == pytest.approx(v, rel=1e-13)
+    # Schulz on all edges: every face area scales with y^2
+    pp = dict(p, poly=0.2, poly_mask=7)
+    assert orc.mean_volume(pp) == pytest.approx(v * (1 + 0.2**2), rel=1e-12)
+    # only the long edge C scaled: faces AC and BC scale with y, AB not
+    pc = dict(p, poly=0.2, poly_mask=4)
+    assert orc.mean_volume(pc) == pytest.approx(v, rel=1e-12)
