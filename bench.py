@@ -70,6 +70,7 @@ STEP = {
     "ellipsoid_F":   ((15,  0,  0, 15, 0, 1), 25),  # |(aQ_A, bQ_B, cQ_C)| (sqrt), series
     "caps_phase":    ((16,  6,  0,  8, 0, 0), 26),  # cap centre phase: FP64 reduction, sincos polynomials
     "cap_node":      ((37,  6,  0,  0, 0, 0), 58),  # per cap node: sincos of B t, angle sum, 2 J1(x)/x series
+    "hollow_F":      ((62, 18,  0, 21, 3, 0), 93),  # 3 x (FP64 phase reduction, sincos, sin/x), 3 faces
     "py_sq":         ((15,  0,  0,  0, 1, 0), 25),  # A10: series in x^2, 1/(1 + 24 phi G/x)
     "weight":        ((3,   0,  0,  2, 0, 0), 3),   # A11
     "detector":      ((0,   5,  0, 23, 0, 1), 0),   # A12: plane crossing (quotient), pixel
@@ -95,6 +96,8 @@ PATHS = {
     "oriented_barbell": COMMON + ["philox_block"] * 3 + ["uniform"] * 10
                         + ["qvec"] + ["orient_angle"] * 2 + ["project_c", "cylinder_F", "caps_phase"]
                         + ["cap_node"] * 76,
+    "oriented_hollow_prism": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
+                             + ["qvec"] + ["orient_angle"] * 3 + ["project_abc", "hollow_F"],
 }
 # Exact-average paths, per quadrature node (76 x 76 = 5776 nodes per neutron),
 # all FP32:
@@ -107,11 +110,15 @@ PATHS = {
 #   capped cylinder (mu x cap nodes): per cap node as in the Monte Carlo path
 #   (cap_node); per mu node Q_AB (sqrt), the cylinder's sinc and 2 J1(x)/x
 #   series, the FP32-reduced cap-centre phase, F^2 and its weight: 57 ops +
-#   6 int + 1 trans32, 83 flops.
+#   6 int + 1 trans32, 83 flops;
+#   thin-walled hollow prism (mu x beta nodes; the C axis' sinc and cos per mu
+#   node): 2 arguments, 2 x (FP32 reduction, sincos polynomials, sin/x), the
+#   three faces, F^2 and its weight: 54 ops + 12 int + 2 trans32, 82 flops;
+#   per mu node 25 ops + 6 int + 1 trans32, 37 flops.
 QUAD_NODE = {"quad_parallelepiped": ((15, 0, 0, 0, 0, 0), 24), "quad_spheroid": ((18, 0, 0, 0, 1, 0), 35),
-             "quad_capped_cylinder": STEP["cap_node"]}
+             "quad_capped_cylinder": STEP["cap_node"], "quad_hollow_prism": ((54, 12, 0, 0, 2, 0), 82)}
 QUAD_MU = {"quad_parallelepiped": ((12, 0, 0, 0, 0, 0), 20), "quad_spheroid": ((0, 0, 0, 0, 0, 0), 0),
-           "quad_capped_cylinder": ((57, 6, 0, 0, 1, 0), 83)}
+           "quad_capped_cylinder": ((57, 6, 0, 0, 1, 0), 83), "quad_hollow_prism": ((25, 6, 0, 0, 1, 0), 37)}
 QUAD_NODES = 76 * 76
 QUAD_BASE = COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["qvec"]
 

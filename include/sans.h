@@ -70,8 +70,11 @@ typedef enum {
     SANS_BARBELL = 5,          /* cylinder R = size[0], L = size[1] (axis C) with
                                   two spherical end caps of radius r = size[2]
                                   >= R whose centres lie outside the cylinder   */
-    SANS_CAPPED_CYLINDER = 6   /* the same cylinder and cap radius, cap centres
+    SANS_CAPPED_CYLINDER = 6,  /* the same cylinder and cap radius, cap centres
                                   inside the cylinder (lens-shaped end caps)    */
+    SANS_HOLLOW_PRISM = 7      /* hollow rectangular prism, outer edges size[0..2]
+                                  along A, B, C, thin walls of thickness shell
+                                  (> 0): the faces as sheets (Tables I-II)     */
 } sans_kind;
 
 /* How the particle size and orientation enter the weight. */

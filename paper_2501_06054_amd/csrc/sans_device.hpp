@@ -428,7 +428,7 @@ __device__ __forceinline__ void project(const Trig3& g, const double qv[3], doub
 
 // ---------------------------------------------------------------- models
 enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParallelepiped = 4,
-              kBarbell = 5, kCappedCylinder = 6 };
+              kBarbell = 5, kCappedCylinder = 6, kHollowPrism = 7 };
 
 // Bodies of revolution about C: cylinder, barbell, capped cylinder (only the
 // axis projection Q.C and Q_AB enter, the third angle does not).
@@ -457,6 +457,36 @@ __device__ __forceinline__ float caps_sum(const TraceArgs& a, float sP, float cP
         sum = __builtin_fmaf(wn[i] * c, lambda1_f(X * sn[i]), sum);
     }
     return sum;
+}
+
+// sin(x)/x and cos x together (thin-walled prism): both from one reduction;
+// the quotient is taken directly (sin x keeps its relative precision down to
+// small x), with 1 at x = 0.
+__device__ __forceinline__ void sinc_cos_d(double xd, float& sn, float& cs)
+{
+    float s, c;
+    sincos_phase(xd, s, c);
+    const float x = (float)xd;
+    sn = x == 0.0f ? 1.0f : s * rcpf(x);
+    cs = c;
+}
+
+__device__ __forceinline__ void sinc_cos_f(float x, float& sn, float& cs)
+{
+    float s, c;
+    sincos_f(x, s, c);
+    sn = x == 0.0f ? 1.0f : s * rcpf(x);
+    cs = c;
+}
+
+// The thin-walled hollow prism's amplitude per unit contrast and wall: each
+// pair of faces normal to an axis contributes 2 cos(half phase) times the
+// face's area and its two in-plane sinc factors (Tables I-II).
+__device__ __forceinline__ float hollow_faces(float a, float b, float c, float sa, float ca, float sb,
+                                              float cb, float sc, float cc)
+{
+    const float sab = sa * sb;
+    return 2.0f * (sc * __builtin_fmaf(b * c * ca, sb, a * c * sa * cb) + a * b * sab * cc);
 }
 
 // F of one drawn particle (MC mode).  y scales the sizes selected by the
@@ -496,6 +526,12 @@ __device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, doub
         const float yf = (float)y;
         const float caps = caps_sum(a, sP, cP, (float)(qcy * a.cap_r), (float)(qab * y));
         return a.contrast * __builtin_fmaf(yf * yf * yf, caps, cyl);
+    } else if constexpr (KIND == kHollowPrism) {
+        float sa, ca, sb, cb, sc, cc;
+        sinc_cos_d(0.5 * qa * s[0], sa, ca);
+        sinc_cos_d(0.5 * qb * s[1], sb, cb);
+        sinc_cos_d(0.5 * qc * s[2], sc, cc);
+        return a.contrast * a.fshell * hollow_faces((float)s[0], (float)s[1], (float)s[2], sa, ca, sb, cb, sc, cc);
     } else {
         return a.contrast * (float)s[0] * (float)s[1] * (float)s[2] * sinc_d(0.5 * qa * s[0])
              * sinc_d(0.5 * qb * s[1]) * sinc_d(0.5 * qc * s[2]);
@@ -532,6 +568,12 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
         sincos_f(qcy * a.fcap_zc, sP, cP);
         const float caps = caps_sum(a, sP, cP, qcy * a.fcap_r, qab * y);
         return a.contrast * __builtin_fmaf(y * y * y, caps, cyl);
+    } else if constexpr (KIND == kHollowPrism) {
+        float sa, ca, sb, cb, sc, cc;
+        sinc_cos_f(0.5f * qa * s[0], sa, ca);
+        sinc_cos_f(0.5f * qb * s[1], sb, cb);
+        sinc_cos_f(0.5f * qc * s[2], sc, cc);
+        return a.contrast * a.fshell * hollow_faces(s[0], s[1], s[2], sa, ca, sb, cb, sc, cc);
     } else {
         return a.contrast * s[0] * s[1] * s[2] * sinc_f(0.5f * qa * s[0]) * sinc_f(0.5f * qb * s[1])
              * sinc_f(0.5f * qc * s[2]);
@@ -600,6 +642,26 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
                     inner = __builtin_fmaf(wb[l], g * g, inner);
                 }
                 avg = __builtin_fmaf(wmu[i] * fc * fc, inner, avg);
+            }
+            avg *= f0 * f0;
+        } else if constexpr (KIND == kHollowPrism) {
+            // the C axis' sinc and cos depend on mu only
+            const float f0 = a.contrast * a.fshell;
+            const float ha = 0.5f * q * s[0], hb = 0.5f * q * s[1], hc = 0.5f * q * s[2];
+            for (int i = i0; i < n; i += istep) {
+                float sc, cc;
+                sinc_cos_f(hc * mu[i], sc, cc);
+                const float xa = ha * stt[i], xb = hb * stt[i];
+                float inner = 0.0f;
+#pragma unroll 2
+                for (int l = 0; l < n; ++l) {
+                    float s_a, c_a, s_b, c_b;
+                    sinc_cos_f(xa * cb[l], s_a, c_a);
+                    sinc_cos_f(xb * sb[l], s_b, c_b);
+                    const float g = hollow_faces(s[0], s[1], s[2], s_a, c_a, s_b, c_b, sc, cc);
+                    inner = __builtin_fmaf(wb[l], g * g, inner);
+                }
+                avg = __builtin_fmaf(wmu[i], inner, avg);
             }
             avg *= f0 * f0;
         } else {

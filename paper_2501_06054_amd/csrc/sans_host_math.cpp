@@ -211,6 +211,15 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
         const double v1 = kPiH * size[0] * size[0] * size[1] + vcaps;
         return v1 * size_moment(poly_kind, poly, mask == 7 ? 3 : 0);
     }
+    case 7: {
+        // wall thickness times the surface 2 (AB + BC + AC); face areas scale
+        // with the product of their two edges' draws
+        const int k0 = b0 ? 1 : 0, k1 = b1 ? 1 : 0, k2 = b2 ? 1 : 0;
+        return 2.0 * shell
+             * (size[0] * size[1] * size_moment(poly_kind, poly, k0 + k1)
+                + size[1] * size[2] * size_moment(poly_kind, poly, k1 + k2)
+                + size[0] * size[2] * size_moment(poly_kind, poly, k0 + k2));
+    }
     }
     return 0.0;
 }

@@ -500,7 +500,8 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 3: batch_tile<3>(a, tl.first, tl.count, hist, tab); break;
         case 4: batch_tile<4>(a, tl.first, tl.count, hist, tab); break;
         case 5: batch_tile<5>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<6>(a, tl.first, tl.count, hist, tab); break;
+        case 6: batch_tile<6>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<7>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -740,6 +741,7 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(4)
         SANS_CASE(5)
         SANS_CASE(6)
+        SANS_CASE(7)
     }
 #undef SANS_CASE
     return nullptr;
@@ -761,6 +763,7 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(4)
         SANS_CASE(5)
         SANS_CASE(6)
+        SANS_CASE(7)
     }
 #undef SANS_CASE
     return nullptr;
@@ -779,6 +782,7 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(4)
         SANS_CASE(5)
         SANS_CASE(6)
+        SANS_CASE(7)
     }
 #undef SANS_CASE
     return nullptr;
@@ -797,6 +801,7 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(4)
         SANS_CASE(5)
         SANS_CASE(6)
+        SANS_CASE(7)
     }
 #undef SANS_CASE
     return nullptr;
@@ -812,6 +817,7 @@ PqFn pick_pq(int kind)
     case 4: return k_pq_avg<4>;
     case 5: return k_pq_avg<5>;
     case 6: return k_pq_avg<6>;
+    case 7: return k_pq_avg<7>;
     }
     return nullptr;
 }
@@ -859,7 +865,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 6) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 7) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -884,6 +890,8 @@ int validate(const sans_params* p)
     }
     if (p->kind == 1 && !(p->shell >= 0.0 && finite(p->shell)))
         return fail(SANS_E_INVALID_ARG, "shell must be >= 0");
+    if (p->kind == SANS_HOLLOW_PRISM && !(p->shell > 0.0 && finite(p->shell)))
+        return fail(SANS_E_INVALID_ARG, "hollow prism: wall thickness (shell) must be > 0");
     for (int k = 0; k < 3; ++k)
         if (!finite(p->sld[k])) return fail(SANS_E_INVALID_ARG, "sld must be finite");
     if (!(p->phi >= 0.0 && p->phi < 1.0)) return fail(SANS_E_INVALID_ARG, "phi must be in [0, 1)");

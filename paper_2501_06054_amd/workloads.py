@@ -24,9 +24,10 @@ import math
 import numpy as np
 
 KINDS = ("sphere", "core_shell", "cylinder", "ellipsoid", "parallelepiped")
-#: bodies of revolution with spherical caps (Tables I-II, group A); not in the
-#: batched experiment generator
-CAPPED_KINDS = ("barbell", "capped_cylinder")
+#: models beyond the five of the batched experiment generator: bodies of
+#: revolution with spherical caps and the thin-walled hollow prism (Tables
+#: I-II)
+EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism")
 ORIENT_KINDS = ("fixed", "gaussian", "isotropic", "uniform_angles")
 MODES = ("mc", "quad", "surrogate")
 POLY_KINDS = ("schulz", "gaussian")
@@ -147,6 +148,25 @@ def quad_capped_cylinder() -> dict:
                               sld=(1e-6, 0, 0), phi=0.01, orient_kind="isotropic"))
 
 
+def oriented_hollow_prism() -> dict:
+    """Thin-walled hollow rectangular prisms, outer edges 30/50/150 A (A along
+    y, B along z, C along x), walls 2 A, Gaussian angular spread 10 deg on all
+    three angles, 256x256 detector, 1e9 neutrons."""
+    return dict(name="oriented_hollow_prism", n=10**9, seed=10, exp_id=0,
+                params=params(kind="hollow_prism", size=(30.0, 50.0, 150.0), shell=2.0,
+                              sld=(1e-6, 0, 0), phi=0.01, orient_kind="gaussian",
+                              orient_mean=(90 * DEG, 0.0, 90 * DEG),
+                              orient_sigma=(10 * DEG, 10 * DEG, 10 * DEG), nx=256, ny=256))
+
+
+def quad_hollow_prism() -> dict:
+    """Isotropically oriented thin-walled hollow prisms 30x50x150 A (walls
+    2 A), exact 76x76 orientation average per neutron, 128x128, 1e7 neutrons."""
+    return dict(name="quad_hollow_prism", n=10**7, seed=11, exp_id=0,
+                params=params(kind="hollow_prism", mode="quad", size=(30.0, 50.0, 150.0), shell=2.0,
+                              sld=(1e-6, 0, 0), phi=0.01, orient_kind="isotropic"))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -156,6 +176,8 @@ WORKLOADS = {
     "quad_spheroid": quad_spheroid,
     "oriented_barbell": oriented_barbell,
     "quad_capped_cylinder": quad_capped_cylinder,
+    "oriented_hollow_prism": oriented_hollow_prism,
+    "quad_hollow_prism": quad_hollow_prism,
 }
 
 

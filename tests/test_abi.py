@@ -101,9 +101,20 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
     (dict(kind="barbell", size=(20.0, 400.0, 40.0), poly=0.1, poly_mask=3), "SANS_E_UNSUPPORTED"),
     (dict(kind="capped_cylinder", size=(20.0, 400.0, 40.0), quad_n=0), "SANS_E_INVALID_ARG"),
     (dict(kind="barbell", size=(20.0, 400.0, 40.0), quad_n=257), "SANS_E_INVALID_ARG"),
+    (dict(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=0.0), "SANS_E_INVALID_ARG"),
+    (dict(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=1.0, quad_n=0, mode="quad",
+          orient_kind="isotropic"), "SANS_E_INVALID_ARG"),
 ])
 def test_capped_body_params_rejected_without_gpu(S, over, code):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(**over))
     h = C.c_void_p()
     assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == getattr(S, code)
+
+
+def test_unknown_kind_rejected_without_gpu(S):
+    from paper_2501_06054_amd import workloads as W
+    sp = S.to_params(W.params(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=1.0))
+    sp.kind = 8
+    h = C.c_void_p()
+    assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED

@@ -50,7 +50,8 @@ def check_detector(d_gpu, d_orc, where="", count=None, w_max=None):
     largest single weight), a pixel may instead deviate by the sum of the
     per-neutron bar over its neutrons, 1e-4 |pixel| + 1e-5 w_max count: the
     bar for models whose amplitude has zeros inside the Q range (the capped
-    bodies), where a sparse pixel can be one neutron near a zero of F."""
+    bodies, the thin-walled prism), where a sparse pixel can be one neutron
+    near a zero of F."""
     d_gpu = np.asarray(d_gpu)
     assert d_gpu.shape == d_orc.shape
     # same set of hit pixels
@@ -68,7 +69,7 @@ def check_detector(d_gpu, d_orc, where="", count=None, w_max=None):
 
 
 # models judged pixel by pixel with the summed per-neutron bar
-SUMMED_BAR = ("barbell", "capped_cylinder")
+SUMMED_BAR = ("barbell", "capped_cylinder", "hollow_prism")
 
 
 def oracle_detector(p, n, seed, first=0):
@@ -173,6 +174,17 @@ PER_NEUTRON = {
     "quad_capped_cylinder": (dict(W.workload("quad_capped_cylinder")["params"]), 601),
     "quad_poly_barbell_fixed": (W.params(kind="barbell", mode="quad", size=(20, 400, 40), poly=0.1,
                                          poly_mask=7, orient_mean=(math.pi / 2, 0, 0)), 2003),
+    # thin-walled hollow prism
+    "oriented_hollow_prism": (W.workload("oriented_hollow_prism")["params"], 50021),
+    "iso_poly_hollow_prism": (W.params(kind="hollow_prism", size=(40, 60, 200), shell=3.0, poly=0.2,
+                                       poly_mask=7, orient_kind="isotropic"), 30011),
+    "gauss_hollow_prism_uniform_angles": (W.params(kind="hollow_prism", size=(25, 25, 90), shell=1.0,
+                                                   poly=0.15, poly_kind="gaussian", poly_mask=4,
+                                                   orient_kind="uniform_angles"), 30011),
+    "quad_hollow_prism": (dict(W.workload("quad_hollow_prism")["params"]), 601),
+    "quad_poly_hollow_prism_fixed": (W.params(kind="hollow_prism", mode="quad", size=(30, 50, 150),
+                                              shell=2.0, poly=0.2, poly_mask=7,
+                                              orient_mean=(0.4, 1.2, 0.3)), 2003),
 }
 
 
@@ -196,7 +208,7 @@ def test_per_neutron_parity(S, name, first):
 
 DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellipsoid",
              "iso_parallelepiped", "poly_ellipsoid_py", "gauss_coreshell_py", "oriented_barbell",
-             "poly_capped_cylinder_iso"]
+             "poly_capped_cylinder_iso", "oriented_hollow_prism", "iso_poly_hollow_prism"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -213,7 +225,7 @@ def test_detector_parity(S, name, tally):
     m.close()
 
 
-@pytest.mark.parametrize("name", ["quad_parallelepiped", "quad_capped_cylinder"])
+@pytest.mark.parametrize("name", ["quad_parallelepiped", "quad_capped_cylinder", "quad_hollow_prism"])
 def test_quad_detector_parity(S, name):
     p = W.workload(name)["params"]
     n, seed = 6007, 6
@@ -226,7 +238,8 @@ def test_quad_detector_parity(S, name):
 
 
 def test_pq_avg_matches_oracle(S):
-    for name in ("quad_parallelepiped", "quad_spheroid", "quad_coreshell", "quad_capped_cylinder"):
+    for name in ("quad_parallelepiped", "quad_spheroid", "quad_coreshell", "quad_capped_cylinder",
+                 "quad_hollow_prism"):
         p, _ = PER_NEUTRON[name]
         m = S.Model(p)
         qs = np.concatenate([np.linspace(0.0, 0.06, 61), np.geomspace(1e-4, 0.3, 40)])
@@ -325,7 +338,8 @@ def test_full_size_coreshell(S):
     m.close()
 
 
-@pytest.mark.parametrize("name", ["oriented_cylinder", "oriented_ellipsoid", "oriented_barbell"])
+@pytest.mark.parametrize("name", ["oriented_cylinder", "oriented_ellipsoid", "oriented_barbell",
+                                  "oriented_hollow_prism"])
 def test_full_size_sampled(S, name):
     """1e9- and 1e8-neutron workloads: the full run equals the sum of its chunks, and
     windows spread over the whole index range match the oracle neutron by
