@@ -19,7 +19,8 @@ SRC = os.path.join(HERE, "sans_oracle.c")
 SO = os.path.join(HERE, "liboracle.so")
 
 KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelepiped": 4,
-        "barbell": 5, "capped_cylinder": 6, "hollow_prism": 7}
+        "barbell": 5, "capped_cylinder": 6, "hollow_prism": 7,
+        "micelle": 8}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
 POLY_KIND = {"schulz": 0, "gaussian": 1}
@@ -40,6 +41,7 @@ class OrcParams(C.Structure):
         ("nx", C.c_int32), ("ny", C.c_int32),
         ("table_size", C.c_int32), ("quad_n", C.c_int32),
         ("poly_kind", C.c_int32), ("pad_", C.c_int32),
+        ("extra", C.c_double * 4),
     ]
 
 
@@ -93,6 +95,8 @@ def lib():
         L.orc_pq_avg.restype = d
         L.orc_amplitude.argtypes = [P(OrcParams), d, P(d), d, P(d)]
         L.orc_amplitude.restype = d
+        L.orc_form_f2.argtypes = [P(OrcParams), d, P(d), d, P(d)]
+        L.orc_form_f2.restype = d
         L.orc_trace.argtypes = [P(OrcParams), u64, u64, u64, u32, i32, P(d), P(d), P(u64)]
         L.orc_trace.restype = i32
         L.orc_trace_debug.argtypes = [P(OrcParams), u64, u64, u64, u32, P(i32), P(d), P(d)]
@@ -133,6 +137,8 @@ def to_params(p: dict) -> OrcParams:
     o.table_size = int(p["table_size"])
     o.quad_n = int(p["quad_n"])
     o.poly_kind = POLY_KIND[p.get("poly_kind", "schulz")]
+    for k, v in enumerate(p.get("extra", (0.0, 0.0, 0.0, 0.0))):
+        o.extra[k] = float(v)
     return o
 
 
@@ -251,6 +257,15 @@ def amplitude(p: dict, q: float, qvec, y: float = 1.0, angles=None) -> float:
     qv = np.asarray(qvec, dtype=np.float64).copy()
     ang = np.asarray(p["orient_mean"] if angles is None else angles, dtype=np.float64).copy()
     return lib().orc_amplitude(C.byref(o), q, _ptr(qv, C.c_double), y, _ptr(ang, C.c_double))
+
+
+def form_f2(p: dict, q: float, qvec, y: float = 1.0, angles=None) -> float:
+    """F^2 of one particle at one event (the micelle: its scattering per
+    particle, which has incoherent chain terms)."""
+    o = to_params(p)
+    qv = np.asarray(qvec, dtype=np.float64).copy()
+    ang = np.asarray(p["orient_mean"] if angles is None else angles, dtype=np.float64).copy()
+    return lib().orc_form_f2(C.byref(o), q, _ptr(qv, C.c_double), y, _ptr(ang, C.c_double))
 
 
 def trace(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0, nthreads: int = 1,

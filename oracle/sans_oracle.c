@@ -44,11 +44,13 @@ typedef struct {
     int32_t kind;          /* 0 sphere, 1 core-shell sphere, 2 cylinder,
                               3 triaxial ellipsoid, 4 parallelepiped,
                               5 barbell, 6 capped cylinder,
-                              7 hollow rectangular prism with thin walls    */
+                              7 hollow rectangular prism with thin walls,
+                              8 polymer micelle (isotropic)                 */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
-                              hollow prism: outer edges A, B, C            */
+                              hollow prism: outer edges A, B, C |
+                              micelle: core radius, corona chain Rg        */
     double shell;          /* core-shell shell thickness; hollow prism wall   */
     double sld[3];         /* particle (core), shell, solvent                */
     double phi;            /* particle volume fraction, n = phi/<V>          */
@@ -70,6 +72,8 @@ typedef struct {
     int32_t poly_kind;     /* size distribution: 0 Schulz, 1 Gaussian kept
                               only where the size is positive                */
     int32_t pad_;
+    double extra[4];       /* micelle: aggregation number N, core-block and
+                              corona-chain volumes (A^3), penetration d      */
 } orc_params;
 
 /* Surrogate mode (mode 2): a network replaces the exact average; set with
@@ -479,6 +483,52 @@ static double amplitude(int kind, const double s[3], double shell, const double 
     return 0.0;
 }
 
+/* Polymer micelle (Pedersen and Gerstenberg, Macromolecules 29 (1996) 1363):
+ * a homogeneous spherical core of radius R carrying N Gaussian chains of
+ * radius of gyration Rg that start at its surface.  With the excess
+ * scattering lengths of one core block and one chain, b_s and b_c, and
+ * x = (q Rg)^2, the scattering per micelle is the sum of the core's self term,
+ * the chains' self terms (Debye function), core-chain and chain-chain
+ * interference; the chain amplitude is the average of exp(-x t) along the
+ * chain and the chains' centres sit at R + d Rg (spherical average: sinc). */
+static double debye_chain(double x)
+{
+    /* 2 (exp(-x) - 1 + x) / x^2: the double average of exp(-x |t - u|) */
+    if (x < 1e-3) return 1.0 - x / 3.0 + x * x / 12.0 - x * x * x / 60.0;
+    return 2.0 * (expm1(-x) + x) / (x * x);
+}
+
+static double chain_amplitude(double x)
+{
+    /* (1 - exp(-x)) / x: the average of exp(-x t) over t in [0, 1] */
+    if (x < 1e-3) return 1.0 - x / 2.0 + x * x / 6.0 - x * x * x / 24.0;
+    return -expm1(-x) / x;
+}
+
+static double micelle_f2(const double s[3], const double sld[3], const double extra[4], double q)
+{
+    double R = s[0], rg = s[1];
+    double n = extra[0], bs = extra[1] * (sld[0] - sld[2]), bc = extra[2] * (sld[1] - sld[2]);
+    double x = q * rg * q * rg;
+    double core = orc_sph(q * R);
+    double pc = debye_chain(x), ac = chain_amplitude(x);
+    double shell = orc_sinc(q * (R + extra[3] * rg));
+    return n * n * bs * bs * core * core + n * bc * bc * pc + 2.0 * n * n * bs * bc * core * ac * shell
+         + n * (n - 1.0) * bc * bc * ac * ac * shell * shell;
+}
+
+/* The squared amplitude of one particle, or for the micelle its scattering
+ * per particle (it has incoherent chain terms). */
+static double form_f2(const orc_params* p, const double s[3], double q, double qa, double qb, double qc)
+{
+    if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
+    double f = amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc, p->quad_n);
+    return f * f;
+}
+
+/* Orientation matters (kinds 2 to 7). */
+static int anisotropic(int kind) { return kind >= 2 && kind <= 7; }
+
 /* Sizes scaled by the relative size draw y according to the mask. */
 static void scaled_sizes(const orc_params* p, double y, double s[3])
 {
@@ -545,6 +595,8 @@ double orc_mean_volume(const orc_params* p)
     case 6: /* all three sizes scale together (or none): V(y) = V(1) y^3 */
         return (ORC_PI * s[0] * s[0] * s[1] + caps_volume(s, p->kind == 5))
              * size_moment(p, p->poly_mask == 7 ? 3 : 0);
+    case 8: /* N chains, each a core block and a corona chain */
+        return p->extra[0] * (p->extra[1] + p->extra[2]);
     case 7: /* wall volume: thickness times the surface 2 (AB + BC + AC) */
         return 2.0 * p->shell
              * (s[0] * s[1] * size_moment(p, b0 + b1) + s[1] * s[2] * size_moment(p, b1 + b2)
@@ -660,7 +712,7 @@ static double pq_avg_nodes(const orc_params* p, double q, const double qvec[3],
         for (int j = 0; j < n; ++j) yw[j] /= norm;
     }
 
-    int aniso = (p->kind >= 2);
+    int aniso = anisotropic(p->kind);
     int iso = aniso && p->orient_kind == 2;
     /* a spheroid (a = b, scaled alike) needs only the angle to its C axis */
     int one_axis = (p->kind == 2 || p->kind == 5 || p->kind == 6)
@@ -675,21 +727,18 @@ static double pq_avg_nodes(const orc_params* p, double q, const double qvec[3],
         scaled_sizes(p, ys[j], s);
         double avg = 0.0;
         if (!aniso) {
-            double f = amplitude(p->kind, s, p->shell, p->sld, q, 0.0, 0.0, 0.0, p->quad_n);
-            avg = f * f;
+            avg = form_f2(p, s, q, 0.0, 0.0, 0.0);
         } else if (!iso) {
             double qa = qvec[0] * A[0] + qvec[1] * A[1] + qvec[2] * A[2];
             double qb = qvec[0] * B[0] + qvec[1] * B[1] + qvec[2] * B[2];
             double qc = qvec[0] * C[0] + qvec[1] * C[1] + qvec[2] * C[2];
-            double f = amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc, p->quad_n);
-            avg = f * f;
+            avg = form_f2(p, s, q, qa, qb, qc);
         } else if (one_axis) {
             for (int i = 0; i < n; ++i) {
                 double mu = 0.5 * (gx[i] + 1.0);
                 double st = sqrt(1.0 - mu * mu);
                 /* A-B plane direction is irrelevant for a symmetric particle */
-                double f = amplitude(p->kind, s, p->shell, p->sld, q, q * st, 0.0, q * mu, p->quad_n);
-                avg += 0.5 * gw[i] * f * f;
+                avg += 0.5 * gw[i] * form_f2(p, s, q, q * st, 0.0, q * mu);
             }
         } else {
             for (int i = 0; i < n; ++i) {
@@ -698,8 +747,7 @@ static double pq_avg_nodes(const orc_params* p, double q, const double qvec[3],
                 for (int k = 0; k < n; ++k) {
                     double beta = 0.25 * ORC_PI * (gx[k] + 1.0);
                     double qa = q * st * cos(beta), qb = q * st * sin(beta), qc = q * mu;
-                    double f = amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc, p->quad_n);
-                    avg += 0.25 * gw[i] * gw[k] * f * f;
+                    avg += 0.25 * gw[i] * gw[k] * form_f2(p, s, q, qa, qb, qc);
                 }
             }
         }
@@ -728,6 +776,19 @@ double orc_amplitude(const orc_params* p, double q, const double qvec[3], double
     double qb = qvec[0] * B[0] + qvec[1] * B[1] + qvec[2] * B[2];
     double qc = qvec[0] * C[0] + qvec[1] * C[1] + qvec[2] * C[2];
     return amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc, p->quad_n);
+}
+
+/* The squared amplitude (micelle: scattering per particle) at one explicit
+ * event, as orc_amplitude. */
+double orc_form_f2(const orc_params* p, double q, const double qvec[3], double y, const double ang[3])
+{
+    double s[3], A[3], B[3], C[3];
+    scaled_sizes(p, y, s);
+    particle_axes(ang, A, B, C);
+    double qa = qvec[0] * A[0] + qvec[1] * A[1] + qvec[2] * A[2];
+    double qb = qvec[0] * B[0] + qvec[1] * B[1] + qvec[2] * B[2];
+    double qc = qvec[0] * C[0] + qvec[1] * C[1] + qvec[2] * C[2];
+    return form_f2(p, s, q, qa, qb, qc);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -871,8 +932,7 @@ static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_
             ang[1] = 2.0 * ORC_PI * u[10];
             ang[2] = 2.0 * ORC_PI * u[11];
         }
-        double f = orc_amplitude(p, q, qv, y, ang);
-        f2 = f * f;
+        f2 = orc_form_f2(p, q, qv, y, ang);
     } else if (p->mode == 1) {
         f2 = pq_avg_nodes(p, q, qv, cx->gx, cx->gw);
     } else {

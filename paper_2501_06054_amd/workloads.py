@@ -25,9 +25,9 @@ import numpy as np
 
 KINDS = ("sphere", "core_shell", "cylinder", "ellipsoid", "parallelepiped")
 #: models beyond the five of the batched experiment generator: bodies of
-#: revolution with spherical caps and the thin-walled hollow prism (Tables
-#: I-II)
-EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism")
+#: revolution with spherical caps, the thin-walled hollow prism and the
+#: polymer micelle (Tables I-II)
+EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle")
 ORIENT_KINDS = ("fixed", "gaussian", "isotropic", "uniform_angles")
 MODES = ("mc", "quad", "surrogate")
 POLY_KINDS = ("schulz", "gaussian")
@@ -53,6 +53,7 @@ SAMPLE_DEFAULTS = dict(
     poly=0.0, poly_mask=1, poly_kind="schulz",
     orient_kind="fixed", orient_mean=(0.0, 0.0, 0.0), orient_sigma=(0.0, 0.0, 0.0),
     table_size=4096, quad_n=76,
+    extra=(0.0, 0.0, 0.0, 0.0),
 )
 
 
@@ -64,7 +65,7 @@ def params(**over) -> dict:
         if k not in p:
             raise KeyError(f"unknown parameter {k!r}")
         p[k] = v
-    for k in ("size", "sld", "orient_mean", "orient_sigma"):
+    for k in ("size", "sld", "orient_mean", "orient_sigma", "extra"):
         p[k] = tuple(float(x) for x in p[k])
     return p
 

@@ -636,3 +636,94 @@ def test_hollow_prism_volume(orc):
     # only the long edge C scaled: faces AC and BC scale with y, AB not
     pc = dict(p, poly=0.2, poly_mask=4)
     assert orc.mean_volume(pc) == pytest.approx(v, rel=1e-12)
+
+
+# ------------------------------------------------------------------ polymer micelle
+
+SOLV = 6.3e-6
+
+
+def _micelle(**over):
+    base = dict(kind="micelle", size=(40.0, 25.0, 0.0), sld=(0.3e-6, 1.0e-6, SOLV),
+                extra=(60.0, 4000.0, 3500.0, 1.0))
+    base.update(over)
+    return W.params(**base)
+
+
+def _chain_double_average(x, n=64):
+    """int_0^1 int_0^1 exp(-x |t - u|) dt du = 2 int_0^1 int_0^t exp(-x (t - u)) du dt."""
+    g, w = np.polynomial.legendre.leggauss(n)
+    t = 0.5 * (g + 1.0)
+    wt = 0.5 * w
+    u = t[:, None] * 0.5 * (g[None, :] + 1.0)
+    wu = t[:, None] * 0.5 * w[None, :]
+    return 2.0 * float(np.sum(wt[:, None] * wu * np.exp(-x * (t[:, None] - u))))
+
+
+def _chain_single_average(x, n=64):
+    g, w = np.polynomial.legendre.leggauss(n)
+    return float(np.sum(0.5 * w * np.exp(-x * 0.5 * (g + 1.0))))
+
+
+@pytest.mark.parametrize("n,vs,vc,s_core,s_cor", [(60.0, 4000.0, 3500.0, 0.3e-6, 1.0e-6),
+                                                  (1.0, 2000.0, 0.0, 1e-6, 0.0),
+                                                  (150.0, 800.0, 6000.0, 6.0e-6, 0.5e-6)])
+def test_micelle_forward_scattering_is_coherent(orc, n, vs, vc, s_core, s_cor):
+    # q = 0: all core blocks and chains scatter in phase, (N (b_s + b_c))^2
+    p = _micelle(extra=(n, vs, vc, 1.0), sld=(s_core, s_cor, SOLV))
+    bs, bc = vs * (s_core - SOLV), vc * (s_cor - SOLV)
+    assert orc.form_f2(p, 0.0, (0.0, 0.0, 0.0)) == pytest.approx((n * (bs + bc)) ** 2, rel=1e-12)
+    assert orc.mean_volume(p) == pytest.approx(n * (vs + vc), rel=1e-14)
+
+
+@pytest.mark.parametrize("q", [0.0, 1e-3, 0.004, 0.02, 0.05, 0.3])
+def test_micelle_single_chain_is_the_debye_function(orc, q):
+    # one chain and no core contrast: b_c^2 times the chain's double average
+    rg = 25.0
+    p = _micelle(extra=(1.0, 4000.0, 1000.0, 1.0), sld=(SOLV, 1.0e-6, SOLV))
+    bc = 1000.0 * (1.0e-6 - SOLV)
+    ref = bc * bc * _chain_double_average((q * rg) ** 2)
+    assert orc.form_f2(p, q, (0.0, q, 0.0)) == pytest.approx(ref, rel=1e-12)
+
+
+@pytest.mark.parametrize("q", [0.002, 0.01, 0.04, 0.12])
+def test_micelle_chain_interference_terms(orc, q):
+    """Two chains without core contrast: 2 b_c^2 P + 2 b_c^2 (psi sinc)^2, psi
+    the chain's single average, the chains' centres at R + d Rg; one chain
+    with the core: the core-chain cross term 2 b_s b_c Phi psi sinc."""
+    R, rg, d = 40.0, 25.0, 1.3
+    x = (q * rg) ** 2
+    bc = 1000.0 * (1.0e-6 - SOLV)
+    bs = 4000.0 * (0.3e-6 - SOLV)
+    sinc = math.sin(q * (R + d * rg)) / (q * (R + d * rg))
+    psi = _chain_single_average(x)
+    pc = _chain_double_average(x)
+    two = _micelle(extra=(2.0, 4000.0, 1000.0, d), sld=(SOLV, 1.0e-6, SOLV))
+    ref2 = 2 * bc * bc * pc + 2 * bc * bc * (psi * sinc) ** 2
+    assert orc.form_f2(two, q, (q, 0.0, 0.0)) == pytest.approx(ref2, rel=1e-11)
+    one = _micelle(extra=(1.0, 4000.0, 1000.0, d), sld=(0.3e-6, 1.0e-6, SOLV))
+    phi = orc.sph(q * R)
+    ref1 = (bs * phi) ** 2 + bc * bc * pc + 2 * bs * bc * phi * psi * sinc
+    assert orc.form_f2(one, q, (0.0, 0.0, q)) == pytest.approx(ref1, rel=1e-11)
+
+
+def test_micelle_without_chains_is_a_sphere(orc):
+    # no corona contrast and N v_core = the core's volume: the homogeneous sphere
+    R, n = 40.0, 60.0
+    vs = 4.0 / 3.0 * math.pi * R ** 3 / n
+    mic = _micelle(size=(R, 25.0, 0.0), extra=(n, vs, 3500.0, 1.0), sld=(0.3e-6, SOLV, SOLV))
+    sph = W.params(kind="sphere", size=(R, 0.0, 0.0), sld=(0.3e-6, 0.0, SOLV))
+    for q in (0.0, 0.01, 0.07, 0.2):
+        ref = orc.amplitude(sph, q, (0.0, 0.0, q)) ** 2
+        assert orc.form_f2(mic, q, (q, 0.0, 0.0)) == pytest.approx(ref, rel=1e-12, abs=1e-30)
+
+
+def test_micelle_is_isotropic(orc):
+    p = _micelle(orient_kind="isotropic")
+    q = 0.03
+    a = orc.form_f2(p, q, (q, 0.0, 0.0), 1.0, (0.0, 0.0, 0.0))
+    b = orc.form_f2(p, q, (0.0, 0.6 * q, 0.8 * q), 1.0, (1.1, 0.4, 2.0))
+    assert a == pytest.approx(b, rel=1e-14)
+    # the exact average over orientations is the same value
+    pq = dict(p, mode="quad")
+    assert orc.pq_avg(pq, q) == pytest.approx(a, rel=1e-12)
