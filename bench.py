@@ -71,6 +71,7 @@ STEP = {
     "caps_phase":    ((16,  6,  0,  8, 0, 0), 26),  # cap centre phase: FP64 reduction, sincos polynomials
     "cap_node":      ((37,  6,  0,  0, 0, 0), 58),  # per cap node: sincos of B t, angle sum, 2 J1(x)/x series
     "hollow_F":      ((62, 18,  0, 21, 3, 0), 93),  # 3 x (FP64 phase reduction, sincos, sin/x), 3 faces
+    "micelle_F":     ((59,  0,  0,  9, 0, 0), 96),  # core 3 j1(x)/x, sinc, two chain series, the sum
     "py_sq":         ((15,  0,  0,  0, 1, 0), 25),  # A10: series in x^2, 1/(1 + 24 phi G/x)
     "weight":        ((3,   0,  0,  2, 0, 0), 3),   # A11
     "detector":      ((0,   5,  0, 23, 0, 1), 0),   # A12: plane crossing (quotient), pixel
@@ -98,6 +99,7 @@ PATHS = {
                         + ["cap_node"] * 76,
     "oriented_hollow_prism": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
                              + ["qvec"] + ["orient_angle"] * 3 + ["project_abc", "hollow_F"],
+    "micelle_py": COMMON + ["philox_block"] * 3 + ["uniform"] * 9 + ["size_draw", "micelle_F", "py_sq"],
 }
 # Exact-average paths, per quadrature node (76 x 76 = 5776 nodes per neutron),
 # all FP32:

@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define SANS_ABI_VERSION 2u
+#define SANS_ABI_VERSION 3u
 
 /* Status codes. */
 #define SANS_OK 0
@@ -72,9 +72,17 @@ typedef enum {
                                   >= R whose centres lie outside the cylinder   */
     SANS_CAPPED_CYLINDER = 6,  /* the same cylinder and cap radius, cap centres
                                   inside the cylinder (lens-shaped end caps)    */
-    SANS_HOLLOW_PRISM = 7      /* hollow rectangular prism, outer edges size[0..2]
+    SANS_HOLLOW_PRISM = 7,     /* hollow rectangular prism, outer edges size[0..2]
                                   along A, B, C, thin walls of thickness shell
                                   (> 0): the faces as sheets (Tables I-II)     */
+    SANS_POLYMER_MICELLE = 8   /* spherical core of radius size[0] carrying
+                                  extra[0] Gaussian chains of radius of gyration
+                                  size[1] (Tables I-II; the model of Pedersen
+                                  and Gerstenberg): sld = core, corona, solvent;
+                                  extra[1], extra[2]: volume of one core block
+                                  and one corona chain (A^3); extra[3]: the
+                                  chains' penetration factor d (their centres
+                                  at size[0] + d size[1]); isotropic           */
 } sans_kind;
 
 /* How the particle size and orientation enter the weight. */
@@ -177,6 +185,8 @@ typedef struct {
     int32_t tally;           /* sans_tally                                     */
     int32_t poly_kind;       /* sans_poly                                      */
     int32_t reserved;        /* 0                                              */
+    double extra[4];         /* model parameters beyond size and shell (see
+                                sans_kind; unused entries 0)                   */
 } sans_params;
 
 typedef struct sans_model_s* sans_model_t;

@@ -100,6 +100,10 @@ struct TraceArgs {
     const float* cap_nodes;
     double cap_zc, cap_r;
     float fcap_zc, fcap_r;
+    // polymer micelle: N, excess lengths of a core block and a chain (A), the
+    // chains' penetration factor d
+    float mic_n, mic_bs, mic_bc;
+    double mic_d;
     // run
     uint64_t first, n;
     uint32_t seed_lo, seed_hi, exp_id;
@@ -428,7 +432,11 @@ __device__ __forceinline__ void project(const Trig3& g, const double qv[3], doub
 
 // ---------------------------------------------------------------- models
 enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParallelepiped = 4,
-              kBarbell = 5, kCappedCylinder = 6, kHollowPrism = 7 };
+              kBarbell = 5, kCappedCylinder = 6, kHollowPrism = 7, kMicelle = 8 };
+
+// Orientation enters the weight (kinds 2 to 7; the micelle is isotropic).
+template <int KIND>
+constexpr bool kAniso = KIND >= kCylinder && KIND != kMicelle;
 
 // Bodies of revolution about C: cylinder, barbell, capped cylinder (only the
 // axis projection Q.C and Q_AB enter, the third angle does not).
@@ -487,6 +495,59 @@ __device__ __forceinline__ float hollow_faces(float a, float b, float c, float s
 {
     const float sab = sa * sb;
     return 2.0f * (sc * __builtin_fmaf(b * c * ca, sb, a * c * sa * cb) + a * b * sab * cc);
+}
+
+// Polymer micelle (Tables I-II; the model of Pedersen and Gerstenberg): a
+// homogeneous core of radius R with N Gaussian chains (radius of gyration Rg)
+// starting at its surface.  Scattering per micelle, with the excess lengths
+// b_s (core block) and b_c (chain), x = (q Rg)^2, the chain's double average
+// P(x) = 2 (e^-x - 1 + x)/x^2 and single average psi(x) = (1 - e^-x)/x, the
+// core amplitude Phi = 3 j1(qR)/(qR) and sigma = sinc(q (R + d Rg)):
+//   (N (b_s Phi + b_c psi sigma))^2 + N b_c^2 (P - (psi sigma)^2),
+// the coherent micelle plus what the chains' self terms add beyond it.  The
+// phases in FP64, the chain functions in FP32 (series below x = 1).
+template <int K> struct DebyeC {   // 2 (-1)^k / (k + 2)!
+    static constexpr double f(int k) { return k == 0 ? 0.5 : f(k - 1) * (-1.0) / (k + 2); }
+    static constexpr float v = (float)(2.0 * f(K));
+};
+template <int K> struct ChainC {   // (-1)^k / (k + 1)!
+    static constexpr double f(int k) { return k == 0 ? 1.0 : f(k - 1) * (-1.0) / (k + 1); }
+    static constexpr float v = (float)f(K);
+};
+
+__device__ __forceinline__ void chain_functions(float x, float& pdebye, float& psi)
+{
+    if (x < 1.0f) {
+        float p = DebyeC<10>::v, c = ChainC<10>::v;
+        p = __builtin_fmaf(p, x, DebyeC<9>::v);  c = __builtin_fmaf(c, x, ChainC<9>::v);
+        p = __builtin_fmaf(p, x, DebyeC<8>::v);  c = __builtin_fmaf(c, x, ChainC<8>::v);
+        p = __builtin_fmaf(p, x, DebyeC<7>::v);  c = __builtin_fmaf(c, x, ChainC<7>::v);
+        p = __builtin_fmaf(p, x, DebyeC<6>::v);  c = __builtin_fmaf(c, x, ChainC<6>::v);
+        p = __builtin_fmaf(p, x, DebyeC<5>::v);  c = __builtin_fmaf(c, x, ChainC<5>::v);
+        p = __builtin_fmaf(p, x, DebyeC<4>::v);  c = __builtin_fmaf(c, x, ChainC<4>::v);
+        p = __builtin_fmaf(p, x, DebyeC<3>::v);  c = __builtin_fmaf(c, x, ChainC<3>::v);
+        p = __builtin_fmaf(p, x, DebyeC<2>::v);  c = __builtin_fmaf(c, x, ChainC<2>::v);
+        p = __builtin_fmaf(p, x, DebyeC<1>::v);  c = __builtin_fmaf(c, x, ChainC<1>::v);
+        pdebye = __builtin_fmaf(p, x, 1.0f);
+        psi = __builtin_fmaf(c, x, 1.0f);
+    } else {
+        const float e = __expf(-x);
+        const float ix = rcpf(x);
+        psi = (1.0f - e) * ix;
+        pdebye = 2.0f * (e - 1.0f + x) * ix * ix;
+    }
+}
+
+__device__ __forceinline__ float micelle_f2(const TraceArgs& a, double R, double rg, double q)
+{
+    const float core = sph3j_d(q * R);
+    const float sigma = sinc_d(q * __builtin_fma(a.mic_d, rg, R));
+    const float qr = (float)(q * rg);
+    float pc, psi;
+    chain_functions(qr * qr, pc, psi);
+    const float ps = psi * sigma;
+    const float amp = a.mic_n * __builtin_fmaf(a.mic_bs, core, a.mic_bc * ps);
+    return __builtin_fmaf(amp, amp, a.mic_n * a.mic_bc * a.mic_bc * __builtin_fmaf(-ps, ps, pc));
 }
 
 // F of one drawn particle (MC mode).  y scales the sizes selected by the
@@ -605,7 +666,7 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
     const float* ys = lq + kQuadArrays * n;
     const float* wy = lq + kQuadArrays * n + ny;
     float qa0 = 0.0f, qb0 = 0.0f, qc0 = 0.0f;
-    if (a.quad_dims == 0 && KIND >= kCylinder) {
+    if (a.quad_dims == 0 && kAniso<KIND>) {
         qa0 = qv[0] * a.fA[0] + qv[1] * a.fA[1] + qv[2] * a.fA[2];
         qb0 = qv[0] * a.fB[0] + qv[1] * a.fB[1] + qv[2] * a.fB[2];
         qc0 = qv[0] * a.fC[0] + qv[1] * a.fC[1] + qv[2] * a.fC[2];
@@ -621,8 +682,14 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
         for (int c = 0; c < 3; ++c) s[c] = (a.poly_mask >> c & 1) ? a.fsize[c] * y : a.fsize[c];
         float avg = 0.0f;
         if (a.quad_dims == 0) {
-            const float f = amplitude_f<KIND>(a, s, q, qa0, qb0, qc0, y);
-            avg = i0 == 0 ? f * f : 0.0f;
+            float f2;
+            if constexpr (KIND == kMicelle) {
+                f2 = micelle_f2(a, s[0], s[1], (double)q);
+            } else {
+                const float f = amplitude_f<KIND>(a, s, q, qa0, qb0, qc0, y);
+                f2 = f * f;
+            }
+            avg = i0 == 0 ? f2 : 0.0f;
         } else if (a.quad_dims == 1) {
 #pragma unroll 4
             for (int i = i0; i < n; i += istep) {
@@ -765,7 +832,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
 
     // scattering vector in the lab frame (anisotropic models)
     double qvd[3] = {0.0, 0.0, 0.0};
-    if constexpr (KIND >= kCylinder) {
+    if constexpr (kAniso<KIND>) {
         qvd[0] = k * __builtin_fma(s2, px, -t * kx);
         qvd[1] = k * __builtin_fma(s2, py, -t * ky);
         qvd[2] = k * __builtin_fma(s2, pz, -t * kz);
@@ -778,7 +845,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
         if (a.third_block) {
             const U4 r2 = philox4x32_10(ilo, ihi, 2u, a.exp_id, a.seed_lo, a.seed_hi);
             if (a.poly_on) y = fmax(table_lerp(tab_size, a.M, u64(r2.x)), 0.0);
-            if constexpr (KIND >= kCylinder) {
+            if constexpr (kAniso<KIND>) {
                 if (a.orient_kind == 1) {
                     rotate_by(a.ang_sin[0], a.ang_cos[0],
                               a.ang_sigma[0] * table_lerp(tab_norm, a.M, u64(r2.y)), g.st, g.ct);
@@ -802,9 +869,14 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
             }
         }
         double qa = 0.0, qb = 0.0, qc = 0.0;
-        if constexpr (KIND >= kCylinder) project<!kOneAxis<KIND>>(g, qvd, qa, qb, qc);
-        const float f = amplitude_mc<KIND>(a, y, qd, qa, qb, qc);
-        f2 = f * f;
+        if constexpr (kAniso<KIND>) project<!kOneAxis<KIND>>(g, qvd, qa, qb, qc);
+        if constexpr (KIND == kMicelle) {
+            f2 = micelle_f2(a, (a.poly_mask & 1) ? a.size[0] * y : a.size[0],
+                            (a.poly_mask & 2) ? a.size[1] * y : a.size[1], qd);
+        } else {
+            const float f = amplitude_mc<KIND>(a, y, qd, qa, qb, qc);
+            f2 = f * f;
+        }
     } else if constexpr (MODE == 1) {
         const float qv[3] = {(float)qvd[0], (float)qvd[1], (float)qvd[2]};
         f2 = quad_average<KIND>(a, a.quad_nodes, q, qv, part, nparts);

@@ -178,7 +178,8 @@ double size_moment(int poly_kind, double p, int k)
 }
 
 // Number-averaged volume of the particle population.
-double mean_volume(int kind, const double size[3], double shell, double poly, int mask, int poly_kind)
+double mean_volume(int kind, const double size[3], double shell, double poly, int mask, int poly_kind,
+                   const double extra[4])
 {
     const bool b0 = mask & 1, b1 = mask & 2, b2 = mask & 4;
     const double c43 = 4.0 / 3.0 * kPiH;
@@ -220,6 +221,9 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
                 + size[1] * size[2] * size_moment(poly_kind, poly, k1 + k2)
                 + size[0] * size[2] * size_moment(poly_kind, poly, k0 + k2));
     }
+    case 8:
+        // N chains, each a core block and a corona chain (not scaled by y)
+        return extra[0] * (extra[1] + extra[2]);
     }
     return 0.0;
 }

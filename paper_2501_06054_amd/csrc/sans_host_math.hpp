@@ -11,7 +11,9 @@ double schulz_moment(double p, int k);
 double positive_normal_quantile(double u, double p);
 double positive_normal_moment(double p, int k);
 double size_moment(int poly_kind, double p, int k);
-double mean_volume(int kind, const double size[3], double shell, double poly, int mask, int poly_kind);
+// Number-averaged particle volume; extra: the micelle's N and volumes.
+double mean_volume(int kind, const double size[3], double shell, double poly, int mask, int poly_kind,
+                   const double extra[4]);
 // End caps of a barbell (barbell = true) or capped cylinder of radius R,
 // length L, cap radius r >= R: the cap centre's distance from the particle
 // centre, the lowest point t0 (in units of r, from the cap centre) where a cap

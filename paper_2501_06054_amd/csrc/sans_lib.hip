@@ -501,7 +501,8 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 4: batch_tile<4>(a, tl.first, tl.count, hist, tab); break;
         case 5: batch_tile<5>(a, tl.first, tl.count, hist, tab); break;
         case 6: batch_tile<6>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<7>(a, tl.first, tl.count, hist, tab); break;
+        case 7: batch_tile<7>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<8>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -742,6 +743,7 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(5)
         SANS_CASE(6)
         SANS_CASE(7)
+        SANS_CASE(8)
     }
 #undef SANS_CASE
     return nullptr;
@@ -764,6 +766,7 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(5)
         SANS_CASE(6)
         SANS_CASE(7)
+        SANS_CASE(8)
     }
 #undef SANS_CASE
     return nullptr;
@@ -783,6 +786,7 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(5)
         SANS_CASE(6)
         SANS_CASE(7)
+        SANS_CASE(8)
     }
 #undef SANS_CASE
     return nullptr;
@@ -802,6 +806,7 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(5)
         SANS_CASE(6)
         SANS_CASE(7)
+        SANS_CASE(8)
     }
 #undef SANS_CASE
     return nullptr;
@@ -818,6 +823,7 @@ PqFn pick_pq(int kind)
     case 5: return k_pq_avg<5>;
     case 6: return k_pq_avg<6>;
     case 7: return k_pq_avg<7>;
+    case 8: return k_pq_avg<8>;
     }
     return nullptr;
 }
@@ -861,11 +867,14 @@ namespace {
 
 bool finite(double x) { return std::isfinite(x); }
 
+// Orientation enters the weight (the micelle is isotropic).
+bool is_aniso(int kind) { return kind >= SANS_CYLINDER && kind != SANS_POLYMER_MICELLE; }
+
 int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 7) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 8) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -878,7 +887,7 @@ int validate(const sans_params* p)
     }
     if (p->orient_kind < 0 || p->orient_kind > 3) return fail(SANS_E_UNSUPPORTED, "unknown orientation kind");
     if (p->tally < 0 || p->tally > 4) return fail(SANS_E_UNSUPPORTED, "unknown tally strategy");
-    const int nsize = p->kind <= 1 ? 1 : (p->kind == 2 ? 2 : 3);
+    const int nsize = p->kind <= 1 ? 1 : ((p->kind == 2 || p->kind == SANS_POLYMER_MICELLE) ? 2 : 3);
     for (int k = 0; k < nsize; ++k)
         if (!(p->size[k] > 0.0) || !finite(p->size[k])) return fail(SANS_E_INVALID_ARG, "size must be > 0");
     if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
@@ -892,6 +901,15 @@ int validate(const sans_params* p)
         return fail(SANS_E_INVALID_ARG, "shell must be >= 0");
     if (p->kind == SANS_HOLLOW_PRISM && !(p->shell > 0.0 && finite(p->shell)))
         return fail(SANS_E_INVALID_ARG, "hollow prism: wall thickness (shell) must be > 0");
+    if (p->kind == SANS_POLYMER_MICELLE) {
+        if (!(p->extra[0] >= 1.0 && finite(p->extra[0])))
+            return fail(SANS_E_INVALID_ARG, "micelle: aggregation number extra[0] must be >= 1");
+        for (int k = 1; k < 4; ++k)
+            if (!(p->extra[k] >= 0.0 && finite(p->extra[k])))
+                return fail(SANS_E_INVALID_ARG, "micelle: volumes and penetration extra[1..3] must be >= 0");
+        if (!(p->extra[1] + p->extra[2] > 0.0))
+            return fail(SANS_E_INVALID_ARG, "micelle: the chain volume extra[1] + extra[2] must be > 0");
+    }
     for (int k = 0; k < 3; ++k)
         if (!finite(p->sld[k])) return fail(SANS_E_INVALID_ARG, "sld must be finite");
     if (!(p->phi >= 0.0 && p->phi < 1.0)) return fail(SANS_E_INVALID_ARG, "phi must be in [0, 1)");
@@ -925,7 +943,7 @@ int validate(const sans_params* p)
         return fail(SANS_E_INVALID_ARG, "nx*ny must be in 1..2^26");
     if (p->mode == SANS_MODE_QUAD) {
         if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
-        if (p->kind >= 2 && p->orient_kind != SANS_ORIENT_FIXED && p->orient_kind != SANS_ORIENT_ISOTROPIC)
+        if (is_aniso(p->kind) && p->orient_kind != SANS_ORIENT_FIXED && p->orient_kind != SANS_ORIENT_ISOTROPIC)
             return fail(SANS_E_UNSUPPORTED, "quadrature mode averages fixed or isotropic orientations only");
     }
     return SANS_OK;
@@ -998,7 +1016,7 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     a.inv_py = p->ny / p->det_h;
     a.nx = p->nx;
     a.ny = p->ny;
-    *mean_v = host::mean_volume(p->kind, p->size, p->shell, p->poly, p->poly_mask, p->poly_kind);
+    *mean_v = host::mean_volume(p->kind, p->size, p->shell, p->poly, p->poly_mask, p->poly_kind, p->extra);
     const double dOmega = 2.0 * 3.141592653589793 * *omc;
     *wscale = 1e10 * dOmega * p->phi / *mean_v;
     a.wscale = *wscale;
@@ -1011,6 +1029,12 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     }
     a.shell = p->shell;
     a.fshell = (float)p->shell;
+    if (p->kind == SANS_POLYMER_MICELLE) {
+        a.mic_n = (float)p->extra[0];
+        a.mic_bs = (float)(p->extra[1] * (p->sld[0] - p->sld[2]));
+        a.mic_bc = (float)(p->extra[2] * (p->sld[1] - p->sld[2]));
+        a.mic_d = p->extra[3];
+    }
     if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
         double zc, t0, vcaps;
         host::cap_geometry(p->kind == SANS_BARBELL, p->size[0], p->size[1], p->size[2], &zc, &t0, &vcaps);
@@ -1039,7 +1063,7 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     a.poly_on = p->poly > 0.0;
     a.poly_mask = p->poly_mask;
     a.orient_kind = p->orient_kind;
-    const bool aniso = p->kind >= 2;
+    const bool aniso = is_aniso(p->kind);
     a.third_block = p->mode == SANS_MODE_MC && (a.poly_on || (aniso && p->orient_kind != 0));
     a.sq_on = p->sq_phi > 0.0;
     if (a.sq_on) {
@@ -1065,7 +1089,7 @@ int configure(sans_model_s* m, const sans_params* p)
     m->p = *p;
     TraceArgs& a = m->args;
     fill_constants(p, a, &m->mean_v, &m->wscale, &m->omc);
-    const bool aniso = p->kind >= 2;
+    const bool aniso = is_aniso(p->kind);
 
 
     // tables
@@ -1656,7 +1680,7 @@ int sans_pq_avg(sans_model_t m, const float* q, const float* qvec, int64_t n, fl
     if (!m || !q || !out) return fail(SANS_E_INVALID_ARG, "NULL argument");
     if (m->p.mode != SANS_MODE_QUAD) return fail(SANS_E_UNSUPPORTED, "model is not in quadrature mode");
     if (n < 0) return fail(SANS_E_INVALID_ARG, "n < 0");
-    if (m->args.quad_dims == 0 && m->p.kind >= 2 && !qvec)
+    if (m->args.quad_dims == 0 && is_aniso(m->p.kind) && !qvec)
         return fail(SANS_E_INVALID_ARG, "fixed orientation needs qvec");
     if (n == 0) return SANS_OK;
     const LdsLayout lay = layout(m, false);
@@ -1925,7 +1949,7 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
         if (p[e].table_size != M) return fail(SANS_E_INVALID_ARG, "batch: table_size must match");
         if (n_neutrons[e] >= (1ull << 48)) return fail(SANS_E_INVALID_ARG, "batch: neutron count too large");
         any_poly |= p[e].poly > 0.0;
-        any_norm |= p[e].kind >= 2 && p[e].orient_kind == SANS_ORIENT_GAUSSIAN;
+        any_norm |= is_aniso(p[e].kind) && p[e].orient_kind == SANS_ORIENT_GAUSSIAN;
         total_n += (double)n_neutrons[e];
     }
     const int npix = nx * ny;
@@ -1987,7 +2011,7 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
             exps[e].tab_size = c.d_tables + jobs.size() * (size_t)M;
             jobs.push_back(schulz_job(p[e].poly, (unsigned long long)(jobs.size() * (size_t)M)));
         }
-        if (p[e].kind >= 2 && p[e].orient_kind == SANS_ORIENT_GAUSSIAN) exps[e].tab_norm = c.d_norm;
+        if (is_aniso(p[e].kind) && p[e].orient_kind == SANS_ORIENT_GAUSSIAN) exps[e].tab_norm = c.d_norm;
         if (p[e].kind == SANS_BARBELL || p[e].kind == SANS_CAPPED_CYLINDER) {
             const size_t off = host_caps.size();
             host_caps.resize(off + 3 * (size_t)p[e].quad_n);

@@ -15,7 +15,7 @@ import torch  # loaded first so that libsans shares PyTorch's HIP runtime
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsans.so")
 
-SANS_ABI_VERSION = 2
+SANS_ABI_VERSION = 3
 SANS_OK = 0
 SANS_E_INVALID_ARG = -1
 SANS_E_UNSUPPORTED = -2
@@ -25,7 +25,8 @@ SANS_E_DOMAIN = -5
 SANS_ACCUMULATE = 1
 
 KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelepiped": 4,
-        "barbell": 5, "capped_cylinder": 6, "hollow_prism": 7}
+        "barbell": 5, "capped_cylinder": 6, "hollow_prism": 7,
+        "micelle": 8}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 POLY_KIND = {"schulz": 0, "gaussian": 1}
@@ -53,6 +54,7 @@ class sans_params(C.Structure):
         ("det_w", C.c_double), ("det_h", C.c_double), ("det_z", C.c_double),
         ("nx", C.c_int32), ("ny", C.c_int32), ("quad_n", C.c_int32), ("tally", C.c_int32),
         ("poly_kind", C.c_int32), ("reserved", C.c_int32),
+        ("extra", C.c_double * 4),
     ]
 
 
@@ -154,6 +156,8 @@ def to_params(p: dict, tally: str = "auto") -> sans_params:
     s.quad_n = int(p["quad_n"])
     s.tally = TALLY[p.get("tally", tally)]
     s.poly_kind = POLY_KIND[p.get("poly_kind", "schulz")]
+    for k, v in enumerate(p.get("extra", (0.0, 0.0, 0.0, 0.0))):
+        s.extra[k] = float(v)
     return s
 
 

@@ -168,6 +168,17 @@ def quad_hollow_prism() -> dict:
                               sld=(1e-6, 0, 0), phi=0.01, orient_kind="isotropic"))
 
 
+def micelle_py() -> dict:
+    """Polymer micelles: polystyrene-like core R = 40 A (Schulz 0.1) with 60
+    Gaussian chains of Rg = 25 A (core block 4000 A^3, corona chain 3500 A^3,
+    d = 1), SLD core/corona/solvent 1.0e-6/0.5e-6/6.3e-6, hard-sphere S(Q)
+    at volume fraction 0.15 (effective radius 80 A), 256x256, 1e9 neutrons."""
+    return dict(name="micelle_py", n=10**9, seed=12, exp_id=0,
+                params=params(kind="micelle", size=(40.0, 25.0, 0.0), sld=(1.0e-6, 0.5e-6, 6.3e-6),
+                              extra=(60.0, 4000.0, 3500.0, 1.0), phi=0.15, sq_phi=0.15,
+                              sq_radius=80.0, poly=0.1, poly_mask=1, nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -179,6 +190,7 @@ WORKLOADS = {
     "quad_capped_cylinder": quad_capped_cylinder,
     "oriented_hollow_prism": oriented_hollow_prism,
     "quad_hollow_prism": quad_hollow_prism,
+    "micelle_py": micelle_py,
 }
 
 

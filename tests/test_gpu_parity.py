@@ -185,6 +185,15 @@ PER_NEUTRON = {
     "quad_poly_hollow_prism_fixed": (W.params(kind="hollow_prism", mode="quad", size=(30, 50, 150),
                                               shell=2.0, poly=0.2, poly_mask=7,
                                               orient_mean=(0.4, 1.2, 0.3)), 2003),
+    # polymer micelle (isotropic; the chain functions' series/closed-form
+    # switch at (q Rg)^2 = 1 falls inside the Q range)
+    "micelle_py": (W.workload("micelle_py")["params"], 50021),
+    "gauss_micelle_big_rg": (W.params(kind="micelle", size=(60, 45, 0), sld=(2e-6, 0.5e-6, 6.3e-6),
+                                      extra=(120.0, 9000.0, 5000.0, 1.5), poly=0.25, poly_mask=3,
+                                      poly_kind="gaussian", orient_kind="isotropic"), 30011),
+    "quad_micelle_poly": (W.params(kind="micelle", mode="quad", size=(40, 25, 0),
+                                   sld=(1e-6, 0.5e-6, 6.3e-6), extra=(60.0, 4000.0, 3500.0, 1.0),
+                                   poly=0.2, poly_mask=3), 2003),
 }
 
 
@@ -208,7 +217,7 @@ def test_per_neutron_parity(S, name, first):
 
 DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellipsoid",
              "iso_parallelepiped", "poly_ellipsoid_py", "gauss_coreshell_py", "oriented_barbell",
-             "poly_capped_cylinder_iso", "oriented_hollow_prism", "iso_poly_hollow_prism"]
+             "poly_capped_cylinder_iso", "oriented_hollow_prism", "iso_poly_hollow_prism", "micelle_py"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -239,7 +248,7 @@ def test_quad_detector_parity(S, name):
 
 def test_pq_avg_matches_oracle(S):
     for name in ("quad_parallelepiped", "quad_spheroid", "quad_coreshell", "quad_capped_cylinder",
-                 "quad_hollow_prism"):
+                 "quad_hollow_prism", "quad_micelle_poly"):
         p, _ = PER_NEUTRON[name]
         m = S.Model(p)
         qs = np.concatenate([np.linspace(0.0, 0.06, 61), np.geomspace(1e-4, 0.3, 40)])
@@ -339,7 +348,7 @@ def test_full_size_coreshell(S):
 
 
 @pytest.mark.parametrize("name", ["oriented_cylinder", "oriented_ellipsoid", "oriented_barbell",
-                                  "oriented_hollow_prism"])
+                                  "oriented_hollow_prism", "micelle_py"])
 def test_full_size_sampled(S, name):
     """1e9- and 1e8-neutron workloads: the full run equals the sum of its chunks, and
     windows spread over the whole index range match the oracle neutron by
