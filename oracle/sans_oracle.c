@@ -45,12 +45,18 @@ typedef struct {
                               3 triaxial ellipsoid, 4 parallelepiped,
                               5 barbell, 6 capped cylinder,
                               7 hollow rectangular prism with thin walls,
-                              8 polymer micelle (isotropic)                 */
+                              8 polymer micelle (isotropic), 9 hollow
+                              cylinder, 10 core-shell cylinder, 11 core-shell
+                              ellipsoid, 12 hollow prism with thick walls    */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
                               hollow prism: outer edges A, B, C |
-                              micelle: core radius, corona chain Rg        */
+                              micelle: core radius, corona chain Rg |
+                              hollow cylinder: bore radius, length |
+                              core-shell cylinder: core R, core length |
+                              core-shell ellipsoid: core semi-axes |
+                              thick hollow prism: outer edges              */
     double shell;          /* core-shell shell thickness; hollow prism wall   */
     double sld[3];         /* particle (core), shell, solvent                */
     double phi;            /* particle volume fraction, n = phi/<V>          */
@@ -73,7 +79,8 @@ typedef struct {
                               only where the size is positive                */
     int32_t pad_;
     double extra[4];       /* micelle: aggregation number N, core-block and
-                              corona-chain volumes (A^3), penetration d      */
+                              corona-chain volumes (A^3), penetration d;
+                              core-shell cylinder: extra[0] = end-face shell */
 } orc_params;
 
 /* Surrogate mode (mode 2): a network replaces the exact average; set with
@@ -428,10 +435,29 @@ static double caps_volume(const double s[3], int barbell)
     return 2.0 * ORC_PI * r * r * r * ((1.0 - t0) - (1.0 - t0 * t0 * t0) / 3.0);
 }
 
+/* Unit-contrast amplitudes of the homogeneous bodies the layered models are
+ * built from: a cylinder (radius r, length len, axis C), an ellipsoid
+ * (semi-axes a, b, c along A, B, C) and a box (edges a, b, c). */
+static double cyl_amp(double r, double len, double qab, double qc)
+{
+    return ORC_PI * r * r * len * orc_sinc(0.5 * qc * len) * orc_lambda1(qab * r);
+}
+
+static double ell_amp(double a, double b, double c, double qa, double qb, double qc)
+{
+    double x = sqrt((a * qa) * (a * qa) + (b * qb) * (b * qb) + (c * qc) * (c * qc));
+    return 4.0 / 3.0 * ORC_PI * a * b * c * orc_sph(x);
+}
+
+static double box_amp(double a, double b, double c, double qa, double qb, double qc)
+{
+    return a * b * c * orc_sinc(0.5 * qa * a) * orc_sinc(0.5 * qb * b) * orc_sinc(0.5 * qc * c);
+}
+
 /* Amplitude for one set of (possibly scaled) sizes; cap_n is the
  * Gauss-Legendre order of the caps' integral (barbell, capped cylinder). */
 static double amplitude(int kind, const double s[3], double shell, const double sld[3],
-                        double q, double qa, double qb, double qc, int cap_n)
+                        const double extra[4], double q, double qa, double qb, double qc, int cap_n)
 {
     double drho = sld[0] - sld[2];
     switch (kind) {
@@ -479,6 +505,25 @@ static double amplitude(int kind, const double s[3], double shell, const double 
         return drho * 2.0 * shell
              * (b * c * cos(xa) * sb * sc + a * c * sa * cos(xb) * sc + a * b * sa * sb * cos(xc));
     }
+    case 9: { /* hollow cylinder: the cylinder of radius bore + shell minus the bore */
+        double qab2 = q * q - qc * qc;
+        double qab = qab2 > 0.0 ? sqrt(qab2) : 0.0;
+        return drho * (cyl_amp(s[0] + shell, s[1], qab, qc) - cyl_amp(s[0], s[1], qab, qc));
+    }
+    case 10: { /* core-shell cylinder: the core (R, L) in a shell of radial thickness
+                  shell and end-face thickness extra[0]; contrasts as for the
+                  core-shell sphere */
+        double qab2 = q * q - qc * qc;
+        double qab = qab2 > 0.0 ? sqrt(qab2) : 0.0;
+        return (sld[0] - sld[1]) * cyl_amp(s[0], s[1], qab, qc)
+             + (sld[1] - sld[2]) * cyl_amp(s[0] + shell, s[1] + 2.0 * extra[0], qab, qc);
+    }
+    case 11: /* core-shell ellipsoid: the core's semi-axes each grown by shell */
+        return (sld[0] - sld[1]) * ell_amp(s[0], s[1], s[2], qa, qb, qc)
+             + (sld[1] - sld[2]) * ell_amp(s[0] + shell, s[1] + shell, s[2] + shell, qa, qb, qc);
+    case 12: /* hollow prism, walls of thickness shell: the box minus its cavity */
+        return drho * (box_amp(s[0], s[1], s[2], qa, qb, qc)
+                       - box_amp(s[0] - 2.0 * shell, s[1] - 2.0 * shell, s[2] - 2.0 * shell, qa, qb, qc));
     }
     return 0.0;
 }
@@ -522,12 +567,12 @@ static double micelle_f2(const double s[3], const double sld[3], const double ex
 static double form_f2(const orc_params* p, const double s[3], double q, double qa, double qb, double qc)
 {
     if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
-    double f = amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc, p->quad_n);
+    double f = amplitude(p->kind, s, p->shell, p->sld, p->extra, q, qa, qb, qc, p->quad_n);
     return f * f;
 }
 
-/* Orientation matters (kinds 2 to 7). */
-static int anisotropic(int kind) { return kind >= 2 && kind <= 7; }
+/* Orientation matters (every kind from 2 but the micelle). */
+static int anisotropic(int kind) { return kind >= 2 && kind != 8; }
 
 /* Sizes scaled by the relative size draw y according to the mask. */
 static void scaled_sizes(const orc_params* p, double y, double s[3])
@@ -570,6 +615,27 @@ static double size_moment(const orc_params* p, int k)
 
 double orc_size_moment(const orc_params* p, int32_t k) { return size_moment(p, k); }
 
+/* E[prod_{i<n} (alpha_i y^b_i + beta_i)] over the size draw y, expanded into
+ * the moments <y^k> term by term (one term per subset of the factors). */
+static double prod_moment(const orc_params* p, const double* alpha, const double* beta, const int* b, int n)
+{
+    double total = 0.0;
+    for (int mask = 0; mask < (1 << n); ++mask) {
+        double c = 1.0;
+        int k = 0;
+        for (int i = 0; i < n; ++i) {
+            if (mask >> i & 1) {
+                c *= alpha[i];
+                k += b[i];
+            } else {
+                c *= beta[i];
+            }
+        }
+        total += c * size_moment(p, k);
+    }
+    return total;
+}
+
 /* Number-averaged particle volume <V> (n = phi/<V>). */
 double orc_mean_volume(const orc_params* p)
 {
@@ -597,6 +663,25 @@ double orc_mean_volume(const orc_params* p)
              * size_moment(p, p->poly_mask == 7 ? 3 : 0);
     case 8: /* N chains, each a core block and a corona chain */
         return p->extra[0] * (p->extra[1] + p->extra[2]);
+    case 9: { /* pi L ((R + t)^2 - R^2) = pi (L y^b1)(2 R t y^b0 + t^2) */
+        double al[2] = {s[1], 2.0 * s[0] * p->shell}, be[2] = {0.0, p->shell * p->shell};
+        int bb[2] = {b1, b0};
+        return ORC_PI * prod_moment(p, al, be, bb, 2);
+    }
+    case 10: { /* the outer cylinder: pi (R + t)^2 (L + 2 t_face) */
+        double al[3] = {s[0], s[0], s[1]}, be[3] = {p->shell, p->shell, 2.0 * p->extra[0]};
+        int bb[3] = {b0, b0, b1};
+        return ORC_PI * prod_moment(p, al, be, bb, 3);
+    }
+    case 11: { /* the outer ellipsoid: 4/3 pi (a + t)(b + t)(c + t) */
+        double be[3] = {p->shell, p->shell, p->shell};
+        int bb[3] = {b0, b1, b2};
+        return 4.0 / 3.0 * ORC_PI * prod_moment(p, s, be, bb, 3);
+    }
+    case 12: { /* box minus cavity (monodisperse) */
+        double t2 = 2.0 * p->shell;
+        return s[0] * s[1] * s[2] - (s[0] - t2) * (s[1] - t2) * (s[2] - t2);
+    }
     case 7: /* wall volume: thickness times the surface 2 (AB + BC + AC) */
         return 2.0 * p->shell
              * (s[0] * s[1] * size_moment(p, b0 + b1) + s[1] * s[2] * size_moment(p, b1 + b2)
@@ -715,8 +800,8 @@ static double pq_avg_nodes(const orc_params* p, double q, const double qvec[3],
     int aniso = anisotropic(p->kind);
     int iso = aniso && p->orient_kind == 2;
     /* a spheroid (a = b, scaled alike) needs only the angle to its C axis */
-    int one_axis = (p->kind == 2 || p->kind == 5 || p->kind == 6)
-                || (p->kind == 3 && p->size[0] == p->size[1]
+    int one_axis = (p->kind == 2 || p->kind == 5 || p->kind == 6 || p->kind == 9 || p->kind == 10)
+                || ((p->kind == 3 || p->kind == 11) && p->size[0] == p->size[1]
                     && (p->poly_mask & 1) == (p->poly_mask >> 1 & 1));
     double A[3], B[3], C[3];
     particle_axes(p->orient_mean, A, B, C);
@@ -775,7 +860,7 @@ double orc_amplitude(const orc_params* p, double q, const double qvec[3], double
     double qa = qvec[0] * A[0] + qvec[1] * A[1] + qvec[2] * A[2];
     double qb = qvec[0] * B[0] + qvec[1] * B[1] + qvec[2] * B[2];
     double qc = qvec[0] * C[0] + qvec[1] * C[1] + qvec[2] * C[2];
-    return amplitude(p->kind, s, p->shell, p->sld, q, qa, qb, qc, p->quad_n);
+    return amplitude(p->kind, s, p->shell, p->sld, p->extra, q, qa, qb, qc, p->quad_n);
 }
 
 /* The squared amplitude (micelle: scattering per particle) at one explicit

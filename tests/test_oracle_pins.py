@@ -407,7 +407,9 @@ def test_coreshell_total_intensity_unbiased(orc):
 @pytest.mark.parametrize("kind,size", [("cylinder", (20, 400, 0)),
                                        ("parallelepiped", (20, 40, 120)),
                                        ("ellipsoid", (20, 40, 120)),
-                                       ("hollow_prism", (30, 50, 150))])
+                                       ("hollow_prism", (30, 50, 150)),
+                                       ("hollow_cylinder", (25, 150, 0)),
+                                       ("core_shell_ellipsoid", (20, 40, 120))])
 def test_isotropic_mc_matches_quadrature(orc, kind, size):
     # Monte Carlo draws of an isotropic orientation (cos theta uniform) give
     # the same detector total as the exact orientation average
@@ -727,3 +729,126 @@ def test_micelle_is_isotropic(orc):
     # the exact average over orientations is the same value
     pq = dict(p, mode="quad")
     assert orc.pq_avg(pq, q) == pytest.approx(a, rel=1e-12)
+
+
+# ------------------------------------------------------------------ hollow and layered bodies
+
+def _gauss(a, b, n):
+    g, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (b - a) * g + 0.5 * (b + a), 0.5 * (b - a) * w
+
+
+def _cyl_shell_ft(qab, qc, z0, z1, r0, r1, nz=96, nr=48, nphi=96):
+    """int cos(Q.x) dV over z0 <= z <= z1, r0 <= rho <= r1 (all phi), by a
+    product Gauss rule in (z, rho, phi)."""
+    z, wz = _gauss(z0, z1, nz)
+    r, wr = _gauss(r0, r1, nr)
+    ph, wp = _gauss(0.0, 2.0 * math.pi, nphi)
+    arg = qc * z[:, None, None] + qab * r[None, :, None] * np.cos(ph)[None, None, :]
+    return float(np.einsum("i,j,k,ijk->", wz, wr * r, wp, np.cos(arg)))
+
+
+def _box_region_ft(qv, lo, hi, n=24):
+    """int cos(Q.x) dV over the box lo <= x <= hi, product Gauss rule."""
+    (x, wx), (y, wy), (z, wz) = (_gauss(lo[k], hi[k], n) for k in range(3))
+    arg = qv[0] * x[:, None, None] + qv[1] * y[None, :, None] + qv[2] * z[None, None, :]
+    return float(np.einsum("i,j,k,ijk->", wx, wy, wz, np.cos(arg)))
+
+
+@pytest.mark.parametrize("qab,qc", [(0.0, 0.0), (0.04, 0.0), (0.0, 0.03), (0.05, 0.02), (0.11, 0.009)])
+def test_hollow_cylinder_is_the_annulus_transform(orc, qab, qc):
+    ri, t, L = 25.0, 8.0, 150.0
+    p = W.params(kind="hollow_cylinder", size=(ri, L, 0.0), shell=t, sld=(1.0, 0.0, 0.0))
+    got = orc.amplitude(p, math.hypot(qab, qc), (qab, 0.0, qc), 1.0, (0.0, 0.0, 0.0))
+    ref = _cyl_shell_ft(qab, qc, -0.5 * L, 0.5 * L, ri, ri + t)
+    assert got == pytest.approx(ref, rel=1e-9, abs=1e-9 * math.pi * L * ((ri + t) ** 2 - ri ** 2))
+
+
+@pytest.mark.parametrize("qab,qc", [(0.0, 0.0), (0.03, 0.01), (0.0, 0.05), (0.08, 0.0)])
+def test_core_shell_cylinder_is_the_layered_transform(orc, qab, qc):
+    """(rho - rho_solvent) integrated against cos(Q.x): the core, the radial
+    shell beside it and the two end-face shells, each region by quadrature."""
+    R, L, t, tf = 20.0, 120.0, 6.0, 4.0
+    rc, rs, rsol = 2.0e-6, 4.5e-6, 6.3e-6
+    p = W.params(kind="core_shell_cylinder", size=(R, L, 0.0), shell=t, sld=(rc, rs, rsol),
+                 extra=(tf, 0.0, 0.0, 0.0))
+    got = orc.amplitude(p, math.hypot(qab, qc), (0.0, qab, qc), 1.0, (0.0, 0.0, 0.0))
+    core = _cyl_shell_ft(qab, qc, -0.5 * L, 0.5 * L, 0.0, R)
+    side = _cyl_shell_ft(qab, qc, -0.5 * L, 0.5 * L, R, R + t)
+    faces = 2.0 * _cyl_shell_ft(qab, qc, 0.5 * L, 0.5 * L + tf, 0.0, R + t) if qc == 0.0 else (
+        _cyl_shell_ft(qab, qc, 0.5 * L, 0.5 * L + tf, 0.0, R + t)
+        + _cyl_shell_ft(qab, qc, -0.5 * L - tf, -0.5 * L, 0.0, R + t))
+    ref = (rc - rsol) * core + (rs - rsol) * (side + faces)
+    assert got == pytest.approx(ref, rel=1e-9, abs=1e-12 * abs(rc - rsol) * math.pi * R * R * L)
+
+
+def test_core_shell_ellipsoid_reductions(orc):
+    # equal semi-axes: the core-shell sphere; shell SLD = core SLD: the grown ellipsoid
+    cs = W.params(kind="core_shell", size=(30.0, 0.0, 0.0), shell=7.0, sld=(1e-6, 3e-6, 6.3e-6))
+    ce = W.params(kind="core_shell_ellipsoid", size=(30.0, 30.0, 30.0), shell=7.0, sld=(1e-6, 3e-6, 6.3e-6))
+    for qv in ((0.0, 0.0, 0.0), (0.02, 0.0, 0.0), (0.01, 0.03, -0.02), (0.0, 0.0, 0.12)):
+        q = math.sqrt(sum(x * x for x in qv))
+        a = orc.amplitude(ce, q, qv, 1.0, (0.5, 1.0, 2.0))
+        b = orc.amplitude(cs, q, qv)
+        assert a == pytest.approx(b, rel=1e-12, abs=1e-14)
+    ce2 = W.params(kind="core_shell_ellipsoid", size=(20.0, 35.0, 90.0), shell=5.0, sld=(2e-6, 2e-6, 6.3e-6))
+    el = W.params(kind="ellipsoid", size=(25.0, 40.0, 95.0), sld=(2e-6, 0.0, 6.3e-6))
+    for qv in ((0.0, 0.0, 0.0), (0.02, 0.01, 0.0), (0.01, -0.03, 0.02)):
+        q = math.sqrt(sum(x * x for x in qv))
+        ang = (0.3, 0.8, 1.4)
+        assert orc.amplitude(ce2, q, qv, 1.0, ang) == pytest.approx(orc.amplitude(el, q, qv, 1.0, ang),
+                                                                    rel=1e-12, abs=1e-14)
+
+
+@pytest.mark.parametrize("qv", [(0.0, 0.0, 0.0), (0.03, 0.0, 0.0), (0.02, -0.05, 0.01), (0.09, 0.04, 0.06)])
+def test_thick_hollow_prism_is_the_wall_transform(orc, qv):
+    """The six walls as boxes: two x-slabs over the whole section, two
+    y-slabs inside them, two z-slabs inside both; each by quadrature."""
+    a, b, c, t = 40.0, 60.0, 100.0, 5.0
+    p = W.params(kind="hollow_prism_thick", size=(a, b, c), shell=t, sld=(1.0, 0.0, 0.0))
+    got = orc.amplitude(p, math.sqrt(sum(x * x for x in qv)), qv, 1.0, (0.0, 0.0, 0.0))
+    ha, hb, hc = 0.5 * a, 0.5 * b, 0.5 * c
+    ref = 0.0
+    for sgn in (-1.0, 1.0):
+        ref += _box_region_ft(qv, (min(sgn * ha, sgn * (ha - t)), -hb, -hc), (max(sgn * ha, sgn * (ha - t)), hb, hc))
+        ref += _box_region_ft(qv, (-(ha - t), min(sgn * hb, sgn * (hb - t)), -hc),
+                              (ha - t, max(sgn * hb, sgn * (hb - t)), hc))
+        ref += _box_region_ft(qv, (-(ha - t), -(hb - t), min(sgn * hc, sgn * (hc - t))),
+                              (ha - t, hb - t, max(sgn * hc, sgn * (hc - t))))
+    vol = a * b * c - (a - 2 * t) * (b - 2 * t) * (c - 2 * t)
+    assert got == pytest.approx(ref, rel=1e-9, abs=1e-10 * vol)
+    assert orc.mean_volume(p) == pytest.approx(vol, rel=1e-14)
+
+
+def test_thick_hollow_prism_thin_limit(orc):
+    # F(t)/t -> the thin-walled prism per unit wall as t -> 0
+    thin = W.params(kind="hollow_prism", size=(30.0, 50.0, 140.0), shell=1.0, sld=(1.0, 0.0, 0.0))
+    for qv in ((0.02, 0.01, 0.03), (0.05, -0.04, 0.01)):
+        q = math.sqrt(sum(x * x for x in qv))
+        ref = orc.amplitude(thin, q, qv, 1.0, (0.7, 0.3, 1.9))
+        t = 1e-4
+        thick = dict(thin, kind="hollow_prism_thick", shell=t)
+        assert orc.amplitude(thick, q, qv, 1.0, (0.7, 0.3, 1.9)) / t == pytest.approx(ref, rel=1e-3, abs=1e-4 * 30 * 140)
+
+
+@pytest.mark.parametrize("kind,size,shell,extra,mask", [
+    ("hollow_cylinder", (25.0, 150.0, 0.0), 8.0, (0.0,) * 4, 3),
+    ("hollow_cylinder", (25.0, 150.0, 0.0), 8.0, (0.0,) * 4, 1),
+    ("core_shell_cylinder", (20.0, 120.0, 0.0), 6.0, (4.0, 0.0, 0.0, 0.0), 3),
+    ("core_shell_cylinder", (20.0, 120.0, 0.0), 6.0, (4.0, 0.0, 0.0, 0.0), 2),
+    ("core_shell_ellipsoid", (20.0, 35.0, 90.0), 5.0, (0.0,) * 4, 7),
+    ("core_shell_ellipsoid", (20.0, 35.0, 90.0), 5.0, (0.0,) * 4, 5),
+])
+def test_layered_mean_volume_by_quadrature(orc, kind, size, shell, extra, mask):
+    """<V> = int V(y) p(y) dy over the Schulz density, with V(y) the volume
+    at unit contrast, F(q = 0), of the scaled body."""
+    from scipy import integrate, stats
+    poly = 0.2
+    p = W.params(kind=kind, size=size, shell=shell, extra=extra, poly=poly, poly_mask=mask,
+                 sld=(1.0, 1.0, 0.0))
+    mono = dict(p, poly=0.0)
+    a = 1.0 / poly ** 2
+    pdf = stats.gamma(a, scale=1.0 / a).pdf
+    vol = lambda y: orc.amplitude(mono, 0.0, (0.0, 0.0, 0.0), y, (0.0, 0.0, 0.0)) * pdf(y)
+    ref, _ = integrate.quad(vol, 0.0, 4.0, limit=200, epsabs=0.0, epsrel=1e-12)
+    assert orc.mean_volume(p) == pytest.approx(ref, rel=1e-9)
