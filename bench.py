@@ -72,6 +72,10 @@ STEP = {
     "cap_node":      ((37,  6,  0,  0, 0, 0), 58),  # per cap node: sincos of B t, angle sum, 2 J1(x)/x series
     "hollow_F":      ((62, 18,  0, 21, 3, 0), 93),  # 3 x (FP64 phase reduction, sincos, sin/x), 3 faces
     "micelle_F":     ((59,  0,  0,  9, 0, 0), 96),  # core 3 j1(x)/x, sinc, two chain series, the sum
+    "cs_cyl_F":      ((50,  0,  0, 28, 0, 2), 80),  # two cylinders (core, outer), contrasts
+    "cs_ell_F":      ((31,  0,  0, 32, 0, 2), 52),  # two ellipsoids (core, outer), contrasts
+    "thick_box_F":   ((68,  0,  0, 15, 0, 0), 122), # box minus cavity: six sinc series
+    "iso_orient":    ((0,   4,  0, 70, 0, 1), 0),   # cos theta = 2u - 1, sin theta (sqrt), two sincospi
     "py_sq":         ((15,  0,  0,  0, 1, 0), 25),  # A10: series in x^2, 1/(1 + 24 phi G/x)
     "weight":        ((3,   0,  0,  2, 0, 0), 3),   # A11
     "detector":      ((0,   5,  0, 23, 0, 1), 0),   # A12: plane crossing (quotient), pixel
@@ -100,6 +104,12 @@ PATHS = {
     "oriented_hollow_prism": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
                              + ["qvec"] + ["orient_angle"] * 3 + ["project_abc", "hollow_F"],
     "micelle_py": COMMON + ["philox_block"] * 3 + ["uniform"] * 9 + ["size_draw", "micelle_F", "py_sq"],
+    "oriented_core_shell_cylinder": COMMON + ["philox_block"] * 3 + ["uniform"] * 10
+                                    + ["qvec"] + ["orient_angle"] * 2 + ["project_c", "cs_cyl_F"],
+    "iso_core_shell_ellipsoid": COMMON + ["philox_block"] * 3 + ["uniform"] * 12
+                                + ["size_draw", "qvec", "iso_orient", "project_abc", "cs_ell_F"],
+    "oriented_hollow_prism_thick": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
+                                   + ["qvec"] + ["orient_angle"] * 3 + ["project_abc", "thick_box_F"],
 }
 # Exact-average paths, per quadrature node (76 x 76 = 5776 nodes per neutron),
 # all FP32:
@@ -116,11 +126,16 @@ PATHS = {
 #   thin-walled hollow prism (mu x beta nodes; the C axis' sinc and cos per mu
 #   node): 2 arguments, 2 x (FP32 reduction, sincos polynomials, sin/x), the
 #   three faces, F^2 and its weight: 54 ops + 12 int + 2 trans32, 82 flops;
-#   per mu node 25 ops + 6 int + 1 trans32, 37 flops.
+#   per mu node 25 ops + 6 int + 1 trans32, 37 flops;
+#   hollow cylinder (size x mu nodes): Q_AB (sqrt), two 2 J1(x)/x series, the
+#   sinc series, the ring, F^2 and its weight: 52 ops + 1 trans32, 79 flops;
+#   per size node 4 ops.
 QUAD_NODE = {"quad_parallelepiped": ((15, 0, 0, 0, 0, 0), 24), "quad_spheroid": ((18, 0, 0, 0, 1, 0), 35),
-             "quad_capped_cylinder": STEP["cap_node"], "quad_hollow_prism": ((54, 12, 0, 0, 2, 0), 82)}
+             "quad_capped_cylinder": STEP["cap_node"], "quad_hollow_prism": ((54, 12, 0, 0, 2, 0), 82),
+             "quad_hollow_cylinder": ((52, 0, 0, 0, 1, 0), 79)}
 QUAD_MU = {"quad_parallelepiped": ((12, 0, 0, 0, 0, 0), 20), "quad_spheroid": ((0, 0, 0, 0, 0, 0), 0),
-           "quad_capped_cylinder": ((57, 6, 0, 0, 1, 0), 83), "quad_hollow_prism": ((25, 6, 0, 0, 1, 0), 37)}
+           "quad_capped_cylinder": ((57, 6, 0, 0, 1, 0), 83), "quad_hollow_prism": ((25, 6, 0, 0, 1, 0), 37),
+           "quad_hollow_cylinder": ((4, 0, 0, 0, 0, 0), 4)}
 QUAD_NODES = 76 * 76
 QUAD_BASE = COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["qvec"]
 

@@ -75,7 +75,7 @@ typedef enum {
     SANS_HOLLOW_PRISM = 7,     /* hollow rectangular prism, outer edges size[0..2]
                                   along A, B, C, thin walls of thickness shell
                                   (> 0): the faces as sheets (Tables I-II)     */
-    SANS_POLYMER_MICELLE = 8   /* spherical core of radius size[0] carrying
+    SANS_POLYMER_MICELLE = 8,  /* spherical core of radius size[0] carrying
                                   extra[0] Gaussian chains of radius of gyration
                                   size[1] (Tables I-II; the model of Pedersen
                                   and Gerstenberg): sld = core, corona, solvent;
@@ -83,6 +83,17 @@ typedef enum {
                                   and one corona chain (A^3); extra[3]: the
                                   chains' penetration factor d (their centres
                                   at size[0] + d size[1]); isotropic           */
+    SANS_HOLLOW_CYLINDER = 9,  /* bore radius size[0], length size[1], wall of
+                                  thickness shell (> 0) around the bore; axis C */
+    SANS_CORE_SHELL_CYLINDER = 10, /* core radius size[0] and length size[1] in
+                                  a shell of radial thickness shell and end-face
+                                  thickness extra[0]; sld = core, shell, solvent */
+    SANS_CORE_SHELL_ELLIPSOID = 11, /* core semi-axes size[0..2] along A, B, C,
+                                  each grown by shell for the outer surface;
+                                  sld = core, shell, solvent                    */
+    SANS_HOLLOW_PRISM_THICK = 12 /* box with outer edges size[0..2] less the
+                                  cavity whose edges are 2 shell shorter
+                                  (0 < 2 shell < every edge; monodisperse)      */
 } sans_kind;
 
 /* How the particle size and orientation enter the weight. */

@@ -104,6 +104,9 @@ struct TraceArgs {
     // chains' penetration factor d
     float mic_n, mic_bs, mic_bc;
     double mic_d;
+    // core-shell cylinder: thickness of the shell on each end face (A)
+    double cs_face;
+    float fcs_face;
     // run
     uint64_t first, n;
     uint32_t seed_lo, seed_hi, exp_id;
@@ -316,6 +319,21 @@ __device__ __forceinline__ float sinc_d(double xd)
     return s * rcpf(x);
 }
 
+// sin(x)/x by its Taylor series to x^10 for |x| <= kSincShortMax (truncation
+// below 6e-10 there): the exact average's inner loops when a whole wave's
+// arguments are known to stay that small.
+constexpr float kSincShortMax = 1.1f;
+__device__ __forceinline__ float sinc_short(float x)
+{
+    const float x2 = x * x;
+    float r = SinC<5>::v;
+    r = __builtin_fmaf(r, x2, SinC<4>::v);
+    r = __builtin_fmaf(r, x2, SinC<3>::v);
+    r = __builtin_fmaf(r, x2, SinC<2>::v);
+    r = __builtin_fmaf(r, x2, SinC<1>::v);
+    return __builtin_fmaf(r, x2, 1.0f);
+}
+
 __device__ __forceinline__ float sinc_f(float x)
 {
     x = fabsf(x);
@@ -432,16 +450,20 @@ __device__ __forceinline__ void project(const Trig3& g, const double qv[3], doub
 
 // ---------------------------------------------------------------- models
 enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParallelepiped = 4,
-              kBarbell = 5, kCappedCylinder = 6, kHollowPrism = 7, kMicelle = 8 };
+              kBarbell = 5, kCappedCylinder = 6, kHollowPrism = 7, kMicelle = 8,
+              kHollowCylinder = 9, kCoreShellCylinder = 10, kCoreShellEllipsoid = 11,
+              kHollowPrismThick = 12 };
 
 // Orientation enters the weight (kinds 2 to 7; the micelle is isotropic).
 template <int KIND>
 constexpr bool kAniso = KIND >= kCylinder && KIND != kMicelle;
 
-// Bodies of revolution about C: cylinder, barbell, capped cylinder (only the
-// axis projection Q.C and Q_AB enter, the third angle does not).
+// Bodies of revolution about C: cylinders (plain, hollow, core-shell),
+// barbell, capped cylinder (only the axis projection Q.C and Q_AB enter, the
+// third angle does not).
 template <int KIND>
-constexpr bool kOneAxis = KIND == kCylinder || KIND == kBarbell || KIND == kCappedCylinder;
+constexpr bool kOneAxis = KIND == kCylinder || KIND == kBarbell || KIND == kCappedCylinder
+                          || KIND == kHollowCylinder || KIND == kCoreShellCylinder;
 
 // The caps' part of the barbell / capped-cylinder amplitude (Tables I-II,
 // group A), in FP32: sum_i w_i cos(P + B t_i) 2J1(X s_i)/(X s_i) over the
@@ -593,6 +615,38 @@ __device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, doub
         sinc_cos_d(0.5 * qb * s[1], sb, cb);
         sinc_cos_d(0.5 * qc * s[2], sc, cc);
         return a.contrast * a.fshell * hollow_faces((float)s[0], (float)s[1], (float)s[2], sa, ca, sb, cb, sc, cc);
+    } else if constexpr (KIND == kHollowCylinder) {
+        // the cylinder of radius bore + wall minus the bore
+        const double qab = sqrt(fmax(__builtin_fma(q, q, -qc * qc), 0.0));
+        const double ro_d = s[0] + a.shell;
+        const float ri = (float)s[0], ro = (float)ro_d;
+        const float ring = ro * ro * lambda1_f((float)(qab * ro_d)) - ri * ri * lambda1_f((float)(qab * s[0]));
+        return a.contrast * (float)kPi * (float)s[1] * sinc_d(0.5 * qc * s[1]) * ring;
+    } else if constexpr (KIND == kCoreShellCylinder) {
+        // core (R, L) and the outer cylinder (R + shell, L + 2 face)
+        const double qab = sqrt(fmax(__builtin_fma(q, q, -qc * qc), 0.0));
+        const double ro_d = s[0] + a.shell, lo_d = __builtin_fma(2.0, a.cs_face, s[1]);
+        const float r = (float)s[0], len = (float)s[1], ro = (float)ro_d, lo = (float)lo_d;
+        const float core = r * r * len * sinc_d(0.5 * qc * s[1]) * lambda1_f((float)(qab * s[0]));
+        const float outer = ro * ro * lo * sinc_d(0.5 * qc * lo_d) * lambda1_f((float)(qab * ro_d));
+        return (float)kPi * __builtin_fmaf(a.cs_core, core, a.cs_shell * outer);
+    } else if constexpr (KIND == kCoreShellEllipsoid) {
+        // the core's semi-axes and the same grown by the shell
+        const double oa = s[0] + a.shell, ob = s[1] + a.shell, oc = s[2] + a.shell;
+        const double xa = qa * s[0], xb = qb * s[1], xc = qc * s[2];
+        const double ya = qa * oa, yb = qb * ob, yc = qc * oc;
+        const float core = (float)s[0] * (float)s[1] * (float)s[2] * sph3j_d(sqrt(xa * xa + xb * xb + xc * xc));
+        const float outer = (float)oa * (float)ob * (float)oc * sph3j_d(sqrt(ya * ya + yb * yb + yc * yc));
+        return k43pi * __builtin_fmaf(a.cs_core, core, a.cs_shell * outer);
+    } else if constexpr (KIND == kHollowPrismThick) {
+        // the box minus its cavity (edges less twice the wall)
+        const double t2 = 2.0 * a.shell;
+        const double ia = s[0] - t2, ib = s[1] - t2, ic = s[2] - t2;
+        const float box = (float)s[0] * (float)s[1] * (float)s[2] * sinc_d(0.5 * qa * s[0])
+                        * sinc_d(0.5 * qb * s[1]) * sinc_d(0.5 * qc * s[2]);
+        const float cav = (float)ia * (float)ib * (float)ic * sinc_d(0.5 * qa * ia) * sinc_d(0.5 * qb * ib)
+                        * sinc_d(0.5 * qc * ic);
+        return a.contrast * (box - cav);
     } else {
         return a.contrast * (float)s[0] * (float)s[1] * (float)s[2] * sinc_d(0.5 * qa * s[0])
              * sinc_d(0.5 * qb * s[1]) * sinc_d(0.5 * qc * s[2]);
@@ -635,6 +689,31 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
         sinc_cos_f(0.5f * qb * s[1], sb, cb);
         sinc_cos_f(0.5f * qc * s[2], sc, cc);
         return a.contrast * a.fshell * hollow_faces(s[0], s[1], s[2], sa, ca, sb, cb, sc, cc);
+    } else if constexpr (KIND == kHollowCylinder) {
+        const float qab = sqrtf(fmaxf(__builtin_fmaf(q, q, -qc * qc), 0.0f));
+        const float ri = s[0], ro = s[0] + a.fshell, len = s[1];
+        const float ring = ro * ro * lambda1_f(qab * ro) - ri * ri * lambda1_f(qab * ri);
+        return a.contrast * (float)kPi * len * sinc_f(0.5f * qc * len) * ring;
+    } else if constexpr (KIND == kCoreShellCylinder) {
+        const float qab = sqrtf(fmaxf(__builtin_fmaf(q, q, -qc * qc), 0.0f));
+        const float r = s[0], len = s[1], ro = s[0] + a.fshell, lo = __builtin_fmaf(2.0f, a.fcs_face, s[1]);
+        const float core = r * r * len * sinc_f(0.5f * qc * len) * lambda1_f(qab * r);
+        const float outer = ro * ro * lo * sinc_f(0.5f * qc * lo) * lambda1_f(qab * ro);
+        return (float)kPi * __builtin_fmaf(a.cs_core, core, a.cs_shell * outer);
+    } else if constexpr (KIND == kCoreShellEllipsoid) {
+        const float oa = s[0] + a.fshell, ob = s[1] + a.fshell, oc = s[2] + a.fshell;
+        const float xa = qa * s[0], xb = qb * s[1], xc = qc * s[2];
+        const float ya = qa * oa, yb = qb * ob, yc = qc * oc;
+        const float core = s[0] * s[1] * s[2] * sph3j_f(sqrtf(xa * xa + xb * xb + xc * xc));
+        const float outer = oa * ob * oc * sph3j_f(sqrtf(ya * ya + yb * yb + yc * yc));
+        return k43pi * __builtin_fmaf(a.cs_core, core, a.cs_shell * outer);
+    } else if constexpr (KIND == kHollowPrismThick) {
+        const float t2 = 2.0f * a.fshell;
+        const float ia = s[0] - t2, ib = s[1] - t2, ic = s[2] - t2;
+        const float box = s[0] * s[1] * s[2] * sinc_f(0.5f * qa * s[0]) * sinc_f(0.5f * qb * s[1])
+                        * sinc_f(0.5f * qc * s[2]);
+        const float cav = ia * ib * ic * sinc_f(0.5f * qa * ia) * sinc_f(0.5f * qb * ib) * sinc_f(0.5f * qc * ic);
+        return a.contrast * (box - cav);
     } else {
         return a.contrast * s[0] * s[1] * s[2] * sinc_f(0.5f * qa * s[0]) * sinc_f(0.5f * qb * s[1])
              * sinc_f(0.5f * qc * s[2]);
@@ -699,16 +778,33 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
         } else if constexpr (KIND == kParallelepiped) {
             const float f0 = a.contrast * s[0] * s[1] * s[2];
             const float ha = 0.5f * q * s[0], hb = 0.5f * q * s[1], hc = 0.5f * q * s[2];
-            for (int i = i0; i < n; i += istep) {
-                const float fc = sinc_f(hc * mu[i]);
-                const float xa = ha * stt[i], xb = hb * stt[i];
-                float inner = 0.0f;
+            // the A and B arguments never exceed ha and hb (|st cb|, |st sb| <= 1):
+            // when they stay within the short series' range across the wave,
+            // every inner node takes it, without a branch
+            if (__all(fmaxf(ha, hb) <= kSincShortMax)) {
+                for (int i = i0; i < n; i += istep) {
+                    const float fc = sinc_f(hc * mu[i]);
+                    const float xa = ha * stt[i], xb = hb * stt[i];
+                    float inner = 0.0f;
 #pragma unroll 4
-                for (int l = 0; l < n; ++l) {
-                    const float g = sinc_f(xa * cb[l]) * sinc_f(xb * sb[l]);
-                    inner = __builtin_fmaf(wb[l], g * g, inner);
+                    for (int l = 0; l < n; ++l) {
+                        const float g = sinc_short(xa * cb[l]) * sinc_short(xb * sb[l]);
+                        inner = __builtin_fmaf(wb[l], g * g, inner);
+                    }
+                    avg = __builtin_fmaf(wmu[i] * fc * fc, inner, avg);
                 }
-                avg = __builtin_fmaf(wmu[i] * fc * fc, inner, avg);
+            } else {
+                for (int i = i0; i < n; i += istep) {
+                    const float fc = sinc_f(hc * mu[i]);
+                    const float xa = ha * stt[i], xb = hb * stt[i];
+                    float inner = 0.0f;
+#pragma unroll 4
+                    for (int l = 0; l < n; ++l) {
+                        const float g = sinc_f(xa * cb[l]) * sinc_f(xb * sb[l]);
+                        inner = __builtin_fmaf(wb[l], g * g, inner);
+                    }
+                    avg = __builtin_fmaf(wmu[i] * fc * fc, inner, avg);
+                }
             }
             avg *= f0 * f0;
         } else if constexpr (KIND == kHollowPrism) {

@@ -177,6 +177,24 @@ double size_moment(int poly_kind, double p, int k)
     return poly_kind == 1 ? positive_normal_moment(p, k) : schulz_moment(p, k);
 }
 
+// E[prod_i (f[i][0] y^k_i + f[i][1])] for three factors: each product term
+// of the expansion takes the moment of its total power of y.
+static double expand_moment(const double f[3][2], const int k[3], int poly_kind, double poly)
+{
+    double total = 0.0;
+    for (int pick = 0; pick < 8; ++pick) {
+        double c = 1.0;
+        int power = 0;
+        for (int i = 0; i < 3; ++i) {
+            const bool scaled = pick >> i & 1;
+            c *= f[i][scaled ? 0 : 1];
+            power += scaled ? k[i] : 0;
+        }
+        total += c * size_moment(poly_kind, poly, power);
+    }
+    return total;
+}
+
 // Number-averaged volume of the particle population.
 double mean_volume(int kind, const double size[3], double shell, double poly, int mask, int poly_kind,
                    const double extra[4])
@@ -224,6 +242,30 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
     case 8:
         // N chains, each a core block and a corona chain (not scaled by y)
         return extra[0] * (extra[1] + extra[2]);
+    case 9: {
+        // pi L ((R + t)^2 - R^2) = pi (L y^b1) (2 R t y^b0 + t^2)
+        const int k0 = b0 ? 1 : 0, k1 = b1 ? 1 : 0;
+        return kPiH * size[1]
+             * (2.0 * size[0] * shell * size_moment(poly_kind, poly, k0 + k1)
+                + shell * shell * size_moment(poly_kind, poly, k1));
+    }
+    case 10: {
+        // the outer cylinder pi (R y^b0 + t)^2 (L y^b1 + 2 t_face)
+        const double f[3][2] = {{size[0], shell}, {size[0], shell}, {size[1], 2.0 * extra[0]}};
+        const int k[3] = {b0 ? 1 : 0, b0 ? 1 : 0, b1 ? 1 : 0};
+        return kPiH * expand_moment(f, k, poly_kind, poly);
+    }
+    case 11: {
+        // the outer ellipsoid 4/3 pi prod (s_i y^b_i + t)
+        const double f[3][2] = {{size[0], shell}, {size[1], shell}, {size[2], shell}};
+        const int k[3] = {b0 ? 1 : 0, b1 ? 1 : 0, b2 ? 1 : 0};
+        return c43 * expand_moment(f, k, poly_kind, poly);
+    }
+    case 12: {
+        // the box minus its cavity (monodisperse)
+        const double t2 = 2.0 * shell;
+        return size[0] * size[1] * size[2] - (size[0] - t2) * (size[1] - t2) * (size[2] - t2);
+    }
     }
     return 0.0;
 }

@@ -502,7 +502,11 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 5: batch_tile<5>(a, tl.first, tl.count, hist, tab); break;
         case 6: batch_tile<6>(a, tl.first, tl.count, hist, tab); break;
         case 7: batch_tile<7>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<8>(a, tl.first, tl.count, hist, tab); break;
+        case 8: batch_tile<8>(a, tl.first, tl.count, hist, tab); break;
+        case 9: batch_tile<9>(a, tl.first, tl.count, hist, tab); break;
+        case 10: batch_tile<10>(a, tl.first, tl.count, hist, tab); break;
+        case 11: batch_tile<11>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<12>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -744,6 +748,10 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(6)
         SANS_CASE(7)
         SANS_CASE(8)
+        SANS_CASE(9)
+        SANS_CASE(10)
+        SANS_CASE(11)
+        SANS_CASE(12)
     }
 #undef SANS_CASE
     return nullptr;
@@ -767,6 +775,10 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(6)
         SANS_CASE(7)
         SANS_CASE(8)
+        SANS_CASE(9)
+        SANS_CASE(10)
+        SANS_CASE(11)
+        SANS_CASE(12)
     }
 #undef SANS_CASE
     return nullptr;
@@ -787,6 +799,10 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(6)
         SANS_CASE(7)
         SANS_CASE(8)
+        SANS_CASE(9)
+        SANS_CASE(10)
+        SANS_CASE(11)
+        SANS_CASE(12)
     }
 #undef SANS_CASE
     return nullptr;
@@ -807,6 +823,10 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(6)
         SANS_CASE(7)
         SANS_CASE(8)
+        SANS_CASE(9)
+        SANS_CASE(10)
+        SANS_CASE(11)
+        SANS_CASE(12)
     }
 #undef SANS_CASE
     return nullptr;
@@ -824,6 +844,10 @@ PqFn pick_pq(int kind)
     case 6: return k_pq_avg<6>;
     case 7: return k_pq_avg<7>;
     case 8: return k_pq_avg<8>;
+    case 9: return k_pq_avg<9>;
+    case 10: return k_pq_avg<10>;
+    case 11: return k_pq_avg<11>;
+    case 12: return k_pq_avg<12>;
     }
     return nullptr;
 }
@@ -874,7 +898,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 8) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 12) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -887,7 +911,9 @@ int validate(const sans_params* p)
     }
     if (p->orient_kind < 0 || p->orient_kind > 3) return fail(SANS_E_UNSUPPORTED, "unknown orientation kind");
     if (p->tally < 0 || p->tally > 4) return fail(SANS_E_UNSUPPORTED, "unknown tally strategy");
-    const int nsize = p->kind <= 1 ? 1 : ((p->kind == 2 || p->kind == SANS_POLYMER_MICELLE) ? 2 : 3);
+    const bool two_sizes = p->kind == SANS_CYLINDER || p->kind == SANS_POLYMER_MICELLE
+                           || p->kind == SANS_HOLLOW_CYLINDER || p->kind == SANS_CORE_SHELL_CYLINDER;
+    const int nsize = p->kind <= 1 ? 1 : (two_sizes ? 2 : 3);
     for (int k = 0; k < nsize; ++k)
         if (!(p->size[k] > 0.0) || !finite(p->size[k])) return fail(SANS_E_INVALID_ARG, "size must be > 0");
     if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
@@ -901,6 +927,19 @@ int validate(const sans_params* p)
         return fail(SANS_E_INVALID_ARG, "shell must be >= 0");
     if (p->kind == SANS_HOLLOW_PRISM && !(p->shell > 0.0 && finite(p->shell)))
         return fail(SANS_E_INVALID_ARG, "hollow prism: wall thickness (shell) must be > 0");
+    if ((p->kind == SANS_CORE_SHELL_CYLINDER || p->kind == SANS_CORE_SHELL_ELLIPSOID)
+        && !(p->shell >= 0.0 && finite(p->shell)))
+        return fail(SANS_E_INVALID_ARG, "shell must be >= 0");
+    if (p->kind == SANS_CORE_SHELL_CYLINDER && !(p->extra[0] >= 0.0 && finite(p->extra[0])))
+        return fail(SANS_E_INVALID_ARG, "core-shell cylinder: face shell extra[0] must be >= 0");
+    if (p->kind == SANS_HOLLOW_CYLINDER && !(p->shell > 0.0 && finite(p->shell)))
+        return fail(SANS_E_INVALID_ARG, "hollow cylinder: wall thickness (shell) must be > 0");
+    if (p->kind == SANS_HOLLOW_PRISM_THICK) {
+        if (!(p->shell > 0.0 && 2.0 * p->shell < std::min(p->size[0], std::min(p->size[1], p->size[2]))))
+            return fail(SANS_E_INVALID_ARG, "thick hollow prism: need 0 < 2 shell < every edge");
+        if (p->poly > 0.0 && p->poly_mask != 0)
+            return fail(SANS_E_UNSUPPORTED, "thick hollow prism: monodisperse edges only");
+    }
     if (p->kind == SANS_POLYMER_MICELLE) {
         if (!(p->extra[0] >= 1.0 && finite(p->extra[0])))
             return fail(SANS_E_INVALID_ARG, "micelle: aggregation number extra[0] must be >= 1");
@@ -1029,6 +1068,10 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     }
     a.shell = p->shell;
     a.fshell = (float)p->shell;
+    if (p->kind == SANS_CORE_SHELL_CYLINDER) {
+        a.cs_face = p->extra[0];
+        a.fcs_face = (float)p->extra[0];
+    }
     if (p->kind == SANS_POLYMER_MICELLE) {
         a.mic_n = (float)p->extra[0];
         a.mic_bs = (float)(p->extra[1] * (p->sld[0] - p->sld[2]));
@@ -1179,10 +1222,12 @@ int configure(sans_model_s* m, const sans_params* p)
         }
         int dims = 0;
         if (aniso && p->orient_kind == SANS_ORIENT_ISOTROPIC) {
-            const bool spheroid = p->kind == 3 && p->size[0] == p->size[1]
+            const bool spheroid = (p->kind == SANS_ELLIPSOID || p->kind == SANS_CORE_SHELL_ELLIPSOID)
+                                  && p->size[0] == p->size[1]
                                   && ((p->poly_mask & 1) != 0) == ((p->poly_mask & 2) != 0);
             dims = (p->kind == SANS_CYLINDER || p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER
-                    || spheroid) ? 1 : 2;
+                    || p->kind == SANS_HOLLOW_CYLINDER || p->kind == SANS_CORE_SHELL_CYLINDER || spheroid)
+                       ? 1 : 2;
         }
         a.quad_n = n;
         a.quad_ny = ny;

@@ -25,9 +25,10 @@ import numpy as np
 
 KINDS = ("sphere", "core_shell", "cylinder", "ellipsoid", "parallelepiped")
 #: models beyond the five of the batched experiment generator: bodies of
-#: revolution with spherical caps, the thin-walled hollow prism and the
+#: revolution with spherical caps, hollow and core-shell bodies and the
 #: polymer micelle (Tables I-II)
-EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle")
+EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle", "hollow_cylinder",
+               "core_shell_cylinder", "core_shell_ellipsoid", "hollow_prism_thick")
 ORIENT_KINDS = ("fixed", "gaussian", "isotropic", "uniform_angles")
 MODES = ("mc", "quad", "surrogate")
 POLY_KINDS = ("schulz", "gaussian")
@@ -179,6 +180,46 @@ def micelle_py() -> dict:
                               sq_radius=80.0, poly=0.1, poly_mask=1, nx=256, ny=256))
 
 
+def oriented_core_shell_cylinder() -> dict:
+    """Core-shell cylinders: core R = 20 A, L = 300 A, shell 5 A (faces 3 A),
+    SLD core/shell/solvent 1e-6/4e-6/6.3e-6, axis along x with Gaussian
+    spread 10 deg, 256x256, 1e9 neutrons."""
+    return dict(name="oriented_core_shell_cylinder", n=10**9, seed=13, exp_id=0,
+                params=params(kind="core_shell_cylinder", size=(20.0, 300.0, 0.0), shell=5.0,
+                              extra=(3.0, 0.0, 0.0, 0.0), sld=(1e-6, 4e-6, 6.3e-6), phi=0.01,
+                              orient_kind="gaussian", orient_mean=(90 * DEG, 0.0, 0.0),
+                              orient_sigma=(10 * DEG, 10 * DEG, 0.0), nx=256, ny=256))
+
+
+def quad_hollow_cylinder() -> dict:
+    """Isotropic hollow cylinders (bore 20 A, wall 6 A, L = 200 A, Schulz 0.15
+    on bore and length), exact average over 76 mu x 76 size nodes, 128x128,
+    1e7 neutrons."""
+    return dict(name="quad_hollow_cylinder", n=10**7, seed=14, exp_id=0,
+                params=params(kind="hollow_cylinder", mode="quad", size=(20.0, 200.0, 0.0), shell=6.0,
+                              sld=(1e-6, 0, 0), phi=0.01, poly=0.15, poly_mask=3,
+                              orient_kind="isotropic"))
+
+
+def iso_core_shell_ellipsoid() -> dict:
+    """Isotropic triaxial core-shell ellipsoids (core 20/30/80 A, shell 5 A,
+    SLD 1e-6/4e-6/6.3e-6, Schulz 0.1 on the core), 256x256, 1e9 neutrons."""
+    return dict(name="iso_core_shell_ellipsoid", n=10**9, seed=15, exp_id=0,
+                params=params(kind="core_shell_ellipsoid", size=(20.0, 30.0, 80.0), shell=5.0,
+                              sld=(1e-6, 4e-6, 6.3e-6), phi=0.01, poly=0.1, poly_mask=7,
+                              orient_kind="isotropic", nx=256, ny=256))
+
+
+def oriented_hollow_prism_thick() -> dict:
+    """Hollow prisms with 5 A walls, outer edges 40/60/150 A, Gaussian spread
+    10 deg on three angles, 256x256, 1e9 neutrons."""
+    return dict(name="oriented_hollow_prism_thick", n=10**9, seed=16, exp_id=0,
+                params=params(kind="hollow_prism_thick", size=(40.0, 60.0, 150.0), shell=5.0,
+                              sld=(1e-6, 0, 0), phi=0.01, orient_kind="gaussian",
+                              orient_mean=(90 * DEG, 0.0, 90 * DEG),
+                              orient_sigma=(10 * DEG, 10 * DEG, 10 * DEG), nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -191,6 +232,10 @@ WORKLOADS = {
     "oriented_hollow_prism": oriented_hollow_prism,
     "quad_hollow_prism": quad_hollow_prism,
     "micelle_py": micelle_py,
+    "oriented_core_shell_cylinder": oriented_core_shell_cylinder,
+    "quad_hollow_cylinder": quad_hollow_cylinder,
+    "iso_core_shell_ellipsoid": iso_core_shell_ellipsoid,
+    "oriented_hollow_prism_thick": oriented_hollow_prism_thick,
 }
 
 

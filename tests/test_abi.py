@@ -108,6 +108,13 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
     (dict(kind="micelle", size=(40.0, 25.0, 0.0), extra=(60.0, -1.0, 3500.0, 1.0)), "SANS_E_INVALID_ARG"),
     (dict(kind="micelle", size=(40.0, 0.0, 0.0), extra=(60.0, 4000.0, 3500.0, 1.0)), "SANS_E_INVALID_ARG"),
     (dict(kind="micelle", size=(40.0, 25.0, 0.0), extra=(60.0, 0.0, 0.0, 1.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="hollow_cylinder", size=(20.0, 100.0, 0.0), shell=0.0), "SANS_E_INVALID_ARG"),
+    (dict(kind="core_shell_cylinder", size=(20.0, 100.0, 0.0), shell=2.0, extra=(-1.0, 0.0, 0.0, 0.0)),
+     "SANS_E_INVALID_ARG"),
+    (dict(kind="core_shell_ellipsoid", size=(20.0, 30.0, 40.0), shell=-1.0), "SANS_E_INVALID_ARG"),
+    (dict(kind="hollow_prism_thick", size=(20.0, 30.0, 40.0), shell=10.0), "SANS_E_INVALID_ARG"),
+    (dict(kind="hollow_prism_thick", size=(20.0, 30.0, 40.0), shell=2.0, poly=0.1, poly_mask=1),
+     "SANS_E_UNSUPPORTED"),
 ])
 def test_capped_body_params_rejected_without_gpu(S, over, code):
     from paper_2501_06054_amd import workloads as W
@@ -119,6 +126,6 @@ def test_capped_body_params_rejected_without_gpu(S, over, code):
 def test_unknown_kind_rejected_without_gpu(S):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=1.0))
-    sp.kind = 9
+    sp.kind = 13
     h = C.c_void_p()
     assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED

@@ -139,15 +139,22 @@ def test_batch_gaussian_sizes(S):
 
 def test_batch_extra_models(S):
     """Barbells and capped cylinders (each experiment with its own cap rule),
-    thin-walled hollow prisms and polymer micelles mixed with the other
-    models: each equals its plain trace, and one of each matches the oracle."""
-    exps = _small_batch(n_exp=10, n_lo=2e5, n_hi=5e5)
+    hollow and core-shell bodies and polymer micelles mixed with the other
+    models: each equals its plain trace, and the extra models match the
+    oracle."""
+    exps = _small_batch(n_exp=14, n_lo=2e5, n_hi=5e5)
     caps = {1: dict(kind="barbell", size=(20.0, 300.0, 35.0), poly_mask=7, quad_n=40),
             4: dict(kind="capped_cylinder", size=(30.0, 120.0, 45.0), poly=0.1, poly_mask=7, quad_n=23),
             7: dict(kind="barbell", size=(15.0, 80.0, 15.0), poly_mask=7, quad_n=76),
             8: dict(kind="hollow_prism", size=(30.0, 50.0, 150.0), shell=2.0, poly_mask=7),
             9: dict(kind="micelle", size=(40.0, 25.0, 0.0), sld=(1e-6, 0.5e-6, 6.3e-6),
-                    extra=(60.0, 4000.0, 3500.0, 1.0), poly_mask=3)}
+                    extra=(60.0, 4000.0, 3500.0, 1.0), poly_mask=3),
+            10: dict(kind="hollow_cylinder", size=(20.0, 150.0, 0.0), shell=6.0, poly_mask=3),
+            11: dict(kind="core_shell_cylinder", size=(25.0, 90.0, 0.0), shell=5.0, extra=(2.0, 0.0, 0.0, 0.0),
+                     sld=(1e-6, 4e-6, 6.3e-6), poly_mask=3),
+            12: dict(kind="core_shell_ellipsoid", size=(20.0, 30.0, 70.0), shell=4.0,
+                     sld=(1e-6, 4e-6, 6.3e-6), poly_mask=7),
+            13: dict(kind="hollow_prism_thick", size=(40.0, 60.0, 150.0), shell=5.0, poly_mask=0)}
     for e, over in caps.items():
         exps[e]["params"] = dict(exps[e]["params"], **over)
     got = _run_batch(S, exps)
@@ -156,7 +163,7 @@ def test_batch_extra_models(S):
         ref = m.trace(x["n"], x["seed"], exp_id=e).cpu().numpy()
         m.close()
         assert np.allclose(got[e], ref, rtol=1e-9, atol=0), e
-    for e in (1, 4, 8, 9):
+    for e in (1, 4, 8, 9, 10, 11, 12, 13):
         x = exps[e]
         ref = oracle.trace(x["params"], x["n"], x["seed"], exp_id=e, nthreads=NTHREADS)
         assert np.array_equal(got[e] != 0, ref != 0), e

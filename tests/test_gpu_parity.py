@@ -194,6 +194,22 @@ PER_NEUTRON = {
     "quad_micelle_poly": (W.params(kind="micelle", mode="quad", size=(40, 25, 0),
                                    sld=(1e-6, 0.5e-6, 6.3e-6), extra=(60.0, 4000.0, 3500.0, 1.0),
                                    poly=0.2, poly_mask=3), 2003),
+    # hollow and layered bodies
+    "oriented_core_shell_cylinder": (W.workload("oriented_core_shell_cylinder")["params"], 50021),
+    "iso_poly_hollow_cylinder": (W.params(kind="hollow_cylinder", size=(15, 120, 0), shell=10.0, poly=0.2,
+                                          poly_mask=3, orient_kind="isotropic"), 30011),
+    "quad_hollow_cylinder": (dict(W.workload("quad_hollow_cylinder")["params"]), 601),
+    "iso_core_shell_ellipsoid": (W.workload("iso_core_shell_ellipsoid")["params"], 30011),
+    "quad_core_shell_spheroid_poly": (W.params(kind="core_shell_ellipsoid", mode="quad", size=(25, 25, 70),
+                                               shell=6.0, sld=(1e-6, 4e-6, 6.3e-6), poly=0.15, poly_mask=7,
+                                               orient_kind="isotropic"), 601),
+    "oriented_hollow_prism_thick": (W.workload("oriented_hollow_prism_thick")["params"], 30011),
+    "quad_hollow_prism_thick": (W.params(kind="hollow_prism_thick", mode="quad", size=(30, 50, 120),
+                                         shell=4.0, orient_kind="isotropic"), 601),
+    "fixed_gauss_core_shell_cylinder": (W.params(kind="core_shell_cylinder", size=(40, 80, 0), shell=10.0,
+                                                 extra=(0.0, 0.0, 0.0, 0.0), sld=(6e-6, 1e-6, 3e-6),
+                                                 poly=0.3, poly_kind="gaussian", poly_mask=1,
+                                                 orient_mean=(0.7, 0.2, 0.0)), 30011),
 }
 
 
@@ -217,7 +233,9 @@ def test_per_neutron_parity(S, name, first):
 
 DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellipsoid",
              "iso_parallelepiped", "poly_ellipsoid_py", "gauss_coreshell_py", "oriented_barbell",
-             "poly_capped_cylinder_iso", "oriented_hollow_prism", "iso_poly_hollow_prism", "micelle_py"]
+             "poly_capped_cylinder_iso", "oriented_hollow_prism", "iso_poly_hollow_prism", "micelle_py",
+             "oriented_core_shell_cylinder", "iso_poly_hollow_cylinder", "iso_core_shell_ellipsoid",
+             "oriented_hollow_prism_thick"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -234,7 +252,8 @@ def test_detector_parity(S, name, tally):
     m.close()
 
 
-@pytest.mark.parametrize("name", ["quad_parallelepiped", "quad_capped_cylinder", "quad_hollow_prism"])
+@pytest.mark.parametrize("name", ["quad_parallelepiped", "quad_capped_cylinder", "quad_hollow_prism",
+                                  "quad_hollow_cylinder"])
 def test_quad_detector_parity(S, name):
     p = W.workload(name)["params"]
     n, seed = 6007, 6
@@ -248,7 +267,8 @@ def test_quad_detector_parity(S, name):
 
 def test_pq_avg_matches_oracle(S):
     for name in ("quad_parallelepiped", "quad_spheroid", "quad_coreshell", "quad_capped_cylinder",
-                 "quad_hollow_prism", "quad_micelle_poly"):
+                 "quad_hollow_prism", "quad_micelle_poly", "quad_hollow_cylinder",
+                 "quad_core_shell_spheroid_poly", "quad_hollow_prism_thick"):
         p, _ = PER_NEUTRON[name]
         m = S.Model(p)
         qs = np.concatenate([np.linspace(0.0, 0.06, 61), np.geomspace(1e-4, 0.3, 40)])
@@ -348,7 +368,7 @@ def test_full_size_coreshell(S):
 
 
 @pytest.mark.parametrize("name", ["oriented_cylinder", "oriented_ellipsoid", "oriented_barbell",
-                                  "oriented_hollow_prism", "micelle_py"])
+                                  "oriented_hollow_prism", "micelle_py", "oriented_core_shell_cylinder"])
 def test_full_size_sampled(S, name):
     """1e9- and 1e8-neutron workloads: the full run equals the sum of its chunks, and
     windows spread over the whole index range match the oracle neutron by
