@@ -47,7 +47,12 @@ typedef struct {
                               7 hollow rectangular prism with thin walls,
                               8 polymer micelle (isotropic), 9 hollow
                               cylinder, 10 core-shell cylinder, 11 core-shell
-                              ellipsoid, 12 hollow prism with thick walls    */
+                              ellipsoid, 12 hollow prism with thick walls;
+                              shape-independent (isotropic, I(q) in 1/cm
+                              with I(0) = extra[0]): 13 Guinier, 14
+                              Ornstein-Zernike, 15 Debye-Anderson-Brumberger,
+                              16 Gaussian coil, 17 polydisperse Gaussian
+                              coil, 18 Teubner-Strey                         */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -562,17 +567,59 @@ static double micelle_f2(const double s[3], const double sld[3], const double ex
          + n * (n - 1.0) * bc * bc * ac * ac * shell * shell;
 }
 
+/* Shape-independent models: the macroscopic cross-section dSigma/dOmega(q)
+ * in 1/cm, scale = its value at q = 0 (extra[0]); the length is size[0]. */
+static int shape_independent(int kind) { return kind >= 13 && kind <= 18; }
+
+static double shape_independent_iq(const orc_params* p, const double s[3], double q)
+{
+    double scale = p->extra[0], l = s[0];
+    double x = q * l * q * l;
+    switch (p->kind) {
+    case 13: /* Guinier: exp(-(q Rg)^2 / 3) */
+        return scale * exp(-x / 3.0);
+    case 14: /* Ornstein-Zernike (Lorentzian), correlation length xi */
+        return scale / (1.0 + x);
+    case 15: /* Debye-Anderson-Brumberger, random two-phase, correlation length */
+        return scale / ((1.0 + x) * (1.0 + x));
+    case 16: /* Gaussian coil: the Debye function of (q Rg)^2 */
+        return scale * debye_chain(x);
+    case 17: { /* Gaussian coils whose masses follow a Schulz-Zimm distribution
+                  (U = Mw/Mn - 1 = extra[1]): the mass-squared weighted average
+                  of the Debye function, 2 ((1 + U z)^(-1/U) - 1 + z) / ((1 + U) z^2)
+                  with z = (q Rg_n)^2 and Rg_n^2 = Rg_z^2 / (1 + 2U), Rg_z the
+                  Guinier (z-average) radius of gyration given in size[0] */
+        double u = p->extra[1];
+        double z = x / (1.0 + 2.0 * u);
+        if (u <= 0.0) return scale * debye_chain(z);
+        if (z < 1e-4) /* series: 1 - z (1 + 2U)/3 + z^2 (1 + 2U)(1 + 3U)/12 */
+            return scale * (1.0 - z * (1.0 + 2.0 * u) / 3.0 + z * z * (1.0 + 2.0 * u) * (1.0 + 3.0 * u) / 12.0);
+        return scale * 2.0 * (pow(1.0 + u * z, -1.0 / u) - 1.0 + z) / ((1.0 + u) * z * z);
+    }
+    case 18: { /* Teubner-Strey: period d = size[1], correlation length xi = size[0];
+                  1/I is a quadratic in q^2 with its minimum at q = 2 pi/d
+                  when d << xi, normalised to I(0) = scale */
+        double k = 2.0 * ORC_PI / s[1], ixi2 = 1.0 / (l * l);
+        double a = (k * k + ixi2) * (k * k + ixi2);
+        return scale * a / (a + 2.0 * (ixi2 - k * k) * q * q + q * q * q * q);
+    }
+    }
+    return 0.0;
+}
+
 /* The squared amplitude of one particle, or for the micelle its scattering
- * per particle (it has incoherent chain terms). */
+ * per particle (it has incoherent chain terms); for the shape-independent
+ * models their cross-section in 1/cm. */
 static double form_f2(const orc_params* p, const double s[3], double q, double qa, double qb, double qc)
 {
+    if (shape_independent(p->kind)) return shape_independent_iq(p, s, q);
     if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
     double f = amplitude(p->kind, s, p->shell, p->sld, p->extra, q, qa, qb, qc, p->quad_n);
     return f * f;
 }
 
-/* Orientation matters (every kind from 2 but the micelle). */
-static int anisotropic(int kind) { return kind >= 2 && kind != 8; }
+/* Orientation matters (the particles from 2 to 12 but the micelle). */
+static int anisotropic(int kind) { return kind >= 2 && kind != 8 && kind <= 12; }
 
 /* Sizes scaled by the relative size draw y according to the mask. */
 static void scaled_sizes(const orc_params* p, double y, double s[3])
@@ -912,7 +959,10 @@ static int ctx_init(orc_ctx* cx, const orc_params* p)
     }
     double sh = sin(0.5 * p->cone_alpha);
     cx->one_minus_cos = 2.0 * sh * sh;
-    cx->prefactor = 2.0 * ORC_PI * cx->one_minus_cos * p->phi / orc_mean_volume(p);
+    /* n F^2 in 1/Angstrom; a shape-independent model gives dSigma/dOmega in
+     * 1/cm directly (1e-8 per Angstrom) */
+    cx->prefactor = 2.0 * ORC_PI * cx->one_minus_cos
+                  * (shape_independent(p->kind) ? 1e-8 : p->phi / orc_mean_volume(p));
     cx->third_block = (p->mode == 0) && (p->poly > 0.0 || p->orient_kind != 0);
     if (p->mode >= 1) {
         if (p->quad_n < 1 || p->quad_n > ORC_MAX_QUAD) return -1;

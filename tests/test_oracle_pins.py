@@ -852,3 +852,100 @@ def test_layered_mean_volume_by_quadrature(orc, kind, size, shell, extra, mask):
     vol = lambda y: orc.amplitude(mono, 0.0, (0.0, 0.0, 0.0), y, (0.0, 0.0, 0.0)) * pdf(y)
     ref, _ = integrate.quad(vol, 0.0, 4.0, limit=200, epsabs=0.0, epsrel=1e-12)
     assert orc.mean_volume(p) == pytest.approx(ref, rel=1e-9)
+
+
+# ------------------------------------------------------------------ shape-independent models
+
+def _radial_transform(gamma, q, rmax, n=4000):
+    """4 pi int_0^rmax r^2 gamma(r) sin(q r)/(q r) dr, composite Gauss rule."""
+    g, w = np.polynomial.legendre.leggauss(16)
+    edges = np.linspace(0.0, rmax, n // 16 + 1)
+    total = 0.0
+    for a, b in zip(edges[:-1], edges[1:]):
+        r = 0.5 * (b - a) * g + 0.5 * (b + a)
+        sinc = np.sinc(q * r / math.pi)
+        total += 0.5 * (b - a) * np.sum(w * r * r * gamma(r) * sinc)
+    return 4.0 * math.pi * total
+
+
+def _si(kind, length, scale=2.5, **over):
+    return W.params(kind=kind, size=(length, over.pop("d", 0.0), 0.0),
+                    extra=(scale, over.pop("u", 0.0), 0.0, 0.0), **over)
+
+
+@pytest.mark.parametrize("q", [0.0, 0.004, 0.02, 0.06])
+def test_guinier_is_a_gaussian_blob(orc, q):
+    # a Gaussian density exp(-r^2 / (2 s^2)) has Rg^2 = 3 s^2 and F = exp(-q^2 s^2 / 2)
+    s = 20.0
+    f = _radial_transform(lambda r: np.exp(-r * r / (2 * s * s)), q, 12 * s)
+    f0 = _radial_transform(lambda r: np.exp(-r * r / (2 * s * s)), 0.0, 12 * s)
+    p = _si("guinier", math.sqrt(3.0) * s)
+    assert orc.form_f2(p, q, (q, 0.0, 0.0)) == pytest.approx(2.5 * (f / f0) ** 2, rel=1e-10)
+
+
+@pytest.mark.parametrize("kind,gamma", [("ornstein_zernike", lambda r, xi: np.exp(-r / xi) / r),
+                                        ("dab", lambda r, xi: np.exp(-r / xi))])
+@pytest.mark.parametrize("q", [0.0, 0.003, 0.02, 0.1])
+def test_correlation_function_models_are_transforms(orc, kind, gamma, q):
+    # Ornstein-Zernike: the transform of exp(-r/xi)/r; DAB: of exp(-r/xi)
+    xi = 35.0
+    t = _radial_transform(lambda r: gamma(r, xi), q, 60 * xi, n=16000)
+    t0 = _radial_transform(lambda r: gamma(r, xi), 0.0, 60 * xi, n=16000)
+    p = _si(kind, xi)
+    assert orc.form_f2(p, q, (0.0, q, 0.0)) == pytest.approx(2.5 * t / t0, rel=1e-8)
+
+
+@pytest.mark.parametrize("q", [0.0, 0.002, 0.01, 0.05, 0.3])
+def test_teubner_strey_is_the_damped_wave_transform(orc, q):
+    # gamma(r) = sin(k r)/(k r) exp(-r/xi), k = 2 pi / d
+    xi, d = 60.0, 150.0
+    k = 2 * math.pi / d
+    gam = lambda r: np.sinc(k * r / math.pi) * np.exp(-r / xi)
+    t = _radial_transform(gam, q, 60 * xi, n=32000)
+    t0 = _radial_transform(gam, 0.0, 60 * xi, n=32000)
+    p = _si("teubner_strey", xi, d=d)
+    assert orc.form_f2(p, q, (0.0, 0.0, q)) == pytest.approx(2.5 * t / t0, rel=1e-7)
+
+
+@pytest.mark.parametrize("q", [0.0, 0.003, 0.01, 0.04, 0.2])
+def test_gauss_coil_is_the_chain_double_average(orc, q):
+    rg = 40.0
+    p = _si("gauss_coil", rg)
+    assert orc.form_f2(p, q, (q, 0.0, 0.0)) == pytest.approx(2.5 * _chain_double_average((q * rg) ** 2),
+                                                             rel=1e-12)
+
+
+@pytest.mark.parametrize("u", [0.0, 0.3, 1.0, 2.5])
+@pytest.mark.parametrize("q", [1e-4, 0.005, 0.02, 0.08])
+def test_poly_gauss_coil_is_the_schulz_mass_average(orc, u, q):
+    """Coils of mass M (Schulz-Zimm number distribution, Mw/Mn = 1 + U) with
+    Rg^2 proportional to M: the M^2-weighted average of the Debye function,
+    by quadrature over M; size[0] is the z-average Rg (the Guinier one)."""
+    from scipy import integrate, special
+    rgz = 50.0
+    p = _si("poly_gauss_coil", rgz, u=u)
+    got = orc.form_f2(p, q, (q, 0.0, 0.0))
+    if u == 0.0:
+        ref = _chain_double_average((q * rgz) ** 2)
+    else:
+        h = 1.0 / u                                  # Schulz shape, Mn = 1
+        b = rgz * rgz / (1.0 + 2.0 * u)              # Rg^2 = b M, <M^3>/<M^2> = 1 + 2U
+        pdf = lambda m: m ** (h - 1) * math.exp(-h * m - special.gammaln(h) + h * math.log(h))
+        def debye(x):
+            return 1.0 - x / 3.0 if x < 1e-8 else 2.0 * (math.expm1(-x) + x) / (x * x)
+        num, _ = integrate.quad(lambda m: pdf(m) * m * m * debye(q * q * b * m), 0, 60, limit=400,
+                                epsabs=0.0, epsrel=1e-12)
+        den, _ = integrate.quad(lambda m: pdf(m) * m * m, 0, 60, limit=400, epsabs=0.0, epsrel=1e-12)
+        ref = num / den
+    assert got == pytest.approx(2.5 * ref, rel=1e-8)
+
+
+def test_shape_independent_weight_units(orc):
+    """A model flat in q (Guinier with a tiny Rg): each neutron's weight is
+    its path length in cm times the cone's solid angle times I in 1/cm."""
+    p = _si("guinier", 1e-6, scale=3.0)
+    ex = orc.trace_debug_ex(p, 2000, 5)
+    hit = ex[:, 0] >= 0
+    omega = 2 * math.pi * (1 - math.cos(p["cone_alpha"]))
+    assert hit.sum() > 1000
+    assert np.allclose(ex[hit, 1], ex[hit, 10] * 100.0 * omega * 3.0, rtol=1e-12)
