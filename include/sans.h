@@ -91,9 +91,21 @@ typedef enum {
     SANS_CORE_SHELL_ELLIPSOID = 11, /* core semi-axes size[0..2] along A, B, C,
                                   each grown by shell for the outer surface;
                                   sld = core, shell, solvent                    */
-    SANS_HOLLOW_PRISM_THICK = 12 /* box with outer edges size[0..2] less the
+    SANS_HOLLOW_PRISM_THICK = 12, /* box with outer edges size[0..2] less the
                                   cavity whose edges are 2 shell shorter
                                   (0 < 2 shell < every edge; monodisperse)      */
+    /* Shape-independent models (Tables I-II): the weight is the macroscopic
+     * cross-section dSigma/dOmega(q) in 1/cm, extra[0] its value at q = 0,
+     * L = size[0] (phi, poly and the structure factor unused: poly > 0 or
+     * sq_phi > 0 is SANS_E_UNSUPPORTED). */
+    SANS_GUINIER = 13,           /* exp(-(q L)^2 / 3), L the radius of gyration */
+    SANS_ORNSTEIN_ZERNIKE = 14,  /* 1 / (1 + (q L)^2), L the correlation length */
+    SANS_DAB = 15,               /* Debye-Anderson-Brumberger 1/(1 + (q L)^2)^2  */
+    SANS_GAUSS_COIL = 16,        /* Debye function of (q L)^2, L the coil's Rg  */
+    SANS_POLY_GAUSS_COIL = 17,   /* coils with Schulz-Zimm masses, U = Mw/Mn - 1
+                                    = extra[1] in [0, 100], L the z-average Rg  */
+    SANS_TEUBNER_STREY = 18      /* microemulsion: correlation length L, period
+                                    size[1]                                    */
 } sans_kind;
 
 /* How the particle size and orientation enter the weight. */

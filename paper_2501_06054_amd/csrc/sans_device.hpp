@@ -104,6 +104,12 @@ struct TraceArgs {
     // chains' penetration factor d
     float mic_n, mic_bs, mic_bc;
     double mic_d;
+    // shape-independent models: I(0) in 1/cm; the polydisperse coil's U and
+    // 1/(1 + 2U); Teubner-Strey's c = 1/xi^2 - k^2, e = 4 k^2/xi^2 and
+    // n = (k^2 + 1/xi^2)^2 (k = 2 pi/d)
+    float si_scale;
+    double si_u, si_z;
+    float ts_c, ts_e, ts_n;
     // core-shell cylinder: thickness of the shell on each end face (A)
     double cs_face;
     float fcs_face;
@@ -452,11 +458,17 @@ __device__ __forceinline__ void project(const Trig3& g, const double qv[3], doub
 enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParallelepiped = 4,
               kBarbell = 5, kCappedCylinder = 6, kHollowPrism = 7, kMicelle = 8,
               kHollowCylinder = 9, kCoreShellCylinder = 10, kCoreShellEllipsoid = 11,
-              kHollowPrismThick = 12 };
+              kHollowPrismThick = 12, kGuinier = 13, kOrnsteinZernike = 14, kDab = 15, kGaussCoil = 16,
+              kPolyGaussCoil = 17, kTeubnerStrey = 18 };
 
-// Orientation enters the weight (kinds 2 to 7; the micelle is isotropic).
+// Shape-independent models: the weight is a cross-section in 1/cm of |Q|.
 template <int KIND>
-constexpr bool kAniso = KIND >= kCylinder && KIND != kMicelle;
+constexpr bool kShapeIndependent = KIND >= kGuinier && KIND <= kTeubnerStrey;
+
+// Orientation enters the weight (the particles from the cylinder on; the
+// micelle and the shape-independent models are isotropic).
+template <int KIND>
+constexpr bool kAniso = KIND >= kCylinder && KIND != kMicelle && !kShapeIndependent<KIND>;
 
 // Bodies of revolution about C: cylinders (plain, hollow, core-shell),
 // barbell, capped cylinder (only the axis projection Q.C and Q_AB enter, the
@@ -570,6 +582,48 @@ __device__ __forceinline__ float micelle_f2(const TraceArgs& a, double R, double
     const float ps = psi * sigma;
     const float amp = a.mic_n * __builtin_fmaf(a.mic_bs, core, a.mic_bc * ps);
     return __builtin_fmaf(amp, amp, a.mic_n * a.mic_bc * a.mic_bc * __builtin_fmaf(-ps, ps, pc));
+}
+
+// Shape-independent models (Tables I-II): dSigma/dOmega(q) in 1/cm with the
+// length L = size[0]: Guinier exp(-(qL)^2/3), Ornstein-Zernike 1/(1 + (qL)^2),
+// Debye-Anderson-Brumberger 1/(1 + (qL)^2)^2, the Gaussian coil's Debye
+// function, coils with Schulz-Zimm masses (the M^2-weighted Debye function,
+// 2 ((1 + U z)^(-1/U) - 1 + z)/((1 + U) z^2), z = (qL)^2/(1 + 2U), the
+// power in FP64 with a series below z = 1e-3), and Teubner-Strey, written as
+// (k^2 + 1/xi^2)^2 / ((q^2 + c)^2 + e) (no cancellation near its peak); all
+// normalised to I(0) = scale.
+template <int KIND>
+__device__ __forceinline__ float shape_iq(const TraceArgs& a, double len, double q)
+{
+    const float ql = (float)(q * len);
+    const float x = ql * ql;
+    if constexpr (KIND == kGuinier) {
+        return a.si_scale * __expf(x * (-1.0f / 3.0f));
+    } else if constexpr (KIND == kOrnsteinZernike) {
+        return a.si_scale * rcpf(1.0f + x);
+    } else if constexpr (KIND == kDab) {
+        const float r = rcpf(1.0f + x);
+        return a.si_scale * r * r;
+    } else if constexpr (KIND == kGaussCoil) {
+        float pc, psi;
+        chain_functions(x, pc, psi);
+        return a.si_scale * pc;
+    } else if constexpr (KIND == kPolyGaussCoil) {
+        const double qld = q * len;
+        const double z = qld * qld * a.si_z, u = a.si_u;
+        double f;
+        if (z < 1e-3) {
+            f = 1.0 - z * (1.0 + 2.0 * u) / 3.0 + z * z * (1.0 + 2.0 * u) * (1.0 + 3.0 * u) / 12.0;
+        } else if (u > 0.0) {
+            f = 2.0 * (pow(1.0 + u * z, -1.0 / u) - 1.0 + z) / ((1.0 + u) * z * z);
+        } else {
+            f = 2.0 * (expm1(-z) + z) / (z * z);
+        }
+        return a.si_scale * (float)f;
+    } else {
+        const float d = (float)(q * q) + a.ts_c;
+        return a.si_scale * a.ts_n * rcpf(__builtin_fmaf(d, d, a.ts_e));
+    }
 }
 
 // F of one drawn particle (MC mode).  y scales the sizes selected by the
@@ -764,6 +818,8 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
             float f2;
             if constexpr (KIND == kMicelle) {
                 f2 = micelle_f2(a, s[0], s[1], (double)q);
+            } else if constexpr (kShapeIndependent<KIND>) {
+                f2 = shape_iq<KIND>(a, a.size[0], (double)q);
             } else {
                 const float f = amplitude_f<KIND>(a, s, q, qa0, qb0, qc0, y);
                 f2 = f * f;
@@ -969,6 +1025,8 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
         if constexpr (KIND == kMicelle) {
             f2 = micelle_f2(a, (a.poly_mask & 1) ? a.size[0] * y : a.size[0],
                             (a.poly_mask & 2) ? a.size[1] * y : a.size[1], qd);
+        } else if constexpr (kShapeIndependent<KIND>) {
+            f2 = shape_iq<KIND>(a, a.size[0], qd);
         } else {
             const float f = amplitude_mc<KIND>(a, y, qd, qa, qb, qc);
             f2 = f * f;

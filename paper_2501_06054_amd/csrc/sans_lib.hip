@@ -506,7 +506,13 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 9: batch_tile<9>(a, tl.first, tl.count, hist, tab); break;
         case 10: batch_tile<10>(a, tl.first, tl.count, hist, tab); break;
         case 11: batch_tile<11>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<12>(a, tl.first, tl.count, hist, tab); break;
+        case 12: batch_tile<12>(a, tl.first, tl.count, hist, tab); break;
+        case 13: batch_tile<13>(a, tl.first, tl.count, hist, tab); break;
+        case 14: batch_tile<14>(a, tl.first, tl.count, hist, tab); break;
+        case 15: batch_tile<15>(a, tl.first, tl.count, hist, tab); break;
+        case 16: batch_tile<16>(a, tl.first, tl.count, hist, tab); break;
+        case 17: batch_tile<17>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<18>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -752,6 +758,12 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(10)
         SANS_CASE(11)
         SANS_CASE(12)
+        SANS_CASE(13)
+        SANS_CASE(14)
+        SANS_CASE(15)
+        SANS_CASE(16)
+        SANS_CASE(17)
+        SANS_CASE(18)
     }
 #undef SANS_CASE
     return nullptr;
@@ -779,6 +791,12 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(10)
         SANS_CASE(11)
         SANS_CASE(12)
+        SANS_CASE(13)
+        SANS_CASE(14)
+        SANS_CASE(15)
+        SANS_CASE(16)
+        SANS_CASE(17)
+        SANS_CASE(18)
     }
 #undef SANS_CASE
     return nullptr;
@@ -803,6 +821,12 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(10)
         SANS_CASE(11)
         SANS_CASE(12)
+        SANS_CASE(13)
+        SANS_CASE(14)
+        SANS_CASE(15)
+        SANS_CASE(16)
+        SANS_CASE(17)
+        SANS_CASE(18)
     }
 #undef SANS_CASE
     return nullptr;
@@ -827,6 +851,12 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(10)
         SANS_CASE(11)
         SANS_CASE(12)
+        SANS_CASE(13)
+        SANS_CASE(14)
+        SANS_CASE(15)
+        SANS_CASE(16)
+        SANS_CASE(17)
+        SANS_CASE(18)
     }
 #undef SANS_CASE
     return nullptr;
@@ -848,6 +878,12 @@ PqFn pick_pq(int kind)
     case 10: return k_pq_avg<10>;
     case 11: return k_pq_avg<11>;
     case 12: return k_pq_avg<12>;
+    case 13: return k_pq_avg<13>;
+    case 14: return k_pq_avg<14>;
+    case 15: return k_pq_avg<15>;
+    case 16: return k_pq_avg<16>;
+    case 17: return k_pq_avg<17>;
+    case 18: return k_pq_avg<18>;
     }
     return nullptr;
 }
@@ -891,14 +927,21 @@ namespace {
 
 bool finite(double x) { return std::isfinite(x); }
 
-// Orientation enters the weight (the micelle is isotropic).
-bool is_aniso(int kind) { return kind >= SANS_CYLINDER && kind != SANS_POLYMER_MICELLE; }
+// Shape-independent models: a cross-section in 1/cm of |Q| only.
+bool is_shape_independent(int kind) { return kind >= SANS_GUINIER && kind <= SANS_TEUBNER_STREY; }
+
+// Orientation enters the weight (the micelle and the shape-independent
+// models are isotropic).
+bool is_aniso(int kind)
+{
+    return kind >= SANS_CYLINDER && kind != SANS_POLYMER_MICELLE && !is_shape_independent(kind);
+}
 
 int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 12) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 18) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -913,7 +956,8 @@ int validate(const sans_params* p)
     if (p->tally < 0 || p->tally > 4) return fail(SANS_E_UNSUPPORTED, "unknown tally strategy");
     const bool two_sizes = p->kind == SANS_CYLINDER || p->kind == SANS_POLYMER_MICELLE
                            || p->kind == SANS_HOLLOW_CYLINDER || p->kind == SANS_CORE_SHELL_CYLINDER;
-    const int nsize = p->kind <= 1 ? 1 : (two_sizes ? 2 : 3);
+    const int nsize = (p->kind <= 1 || (is_shape_independent(p->kind) && p->kind != SANS_TEUBNER_STREY))
+                          ? 1 : (two_sizes || p->kind == SANS_TEUBNER_STREY ? 2 : 3);
     for (int k = 0; k < nsize; ++k)
         if (!(p->size[k] > 0.0) || !finite(p->size[k])) return fail(SANS_E_INVALID_ARG, "size must be > 0");
     if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
@@ -939,6 +983,14 @@ int validate(const sans_params* p)
             return fail(SANS_E_INVALID_ARG, "thick hollow prism: need 0 < 2 shell < every edge");
         if (p->poly > 0.0 && p->poly_mask != 0)
             return fail(SANS_E_UNSUPPORTED, "thick hollow prism: monodisperse edges only");
+    }
+    if (is_shape_independent(p->kind)) {
+        if (!(p->extra[0] >= 0.0 && finite(p->extra[0])))
+            return fail(SANS_E_INVALID_ARG, "shape-independent model: scale extra[0] must be >= 0");
+        if (p->kind == SANS_POLY_GAUSS_COIL && !(p->extra[1] >= 0.0 && p->extra[1] <= 100.0))
+            return fail(SANS_E_INVALID_ARG, "polydisperse coil: U = Mw/Mn - 1 (extra[1]) must be in [0, 100]");
+        if (p->poly > 0.0) return fail(SANS_E_UNSUPPORTED, "shape-independent model: no size distribution");
+        if (p->sq_phi > 0.0) return fail(SANS_E_UNSUPPORTED, "shape-independent model: no structure factor");
     }
     if (p->kind == SANS_POLYMER_MICELLE) {
         if (!(p->extra[0] >= 1.0 && finite(p->extra[0])))
@@ -1057,7 +1109,8 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     a.ny = p->ny;
     *mean_v = host::mean_volume(p->kind, p->size, p->shell, p->poly, p->poly_mask, p->poly_kind, p->extra);
     const double dOmega = 2.0 * 3.141592653589793 * *omc;
-    *wscale = 1e10 * dOmega * p->phi / *mean_v;
+    // n F^2 in 1/Angstrom; a shape-independent model's cross-section is in 1/cm
+    *wscale = 1e10 * dOmega * (is_shape_independent(p->kind) ? 1e-8 : p->phi / *mean_v);
     a.wscale = *wscale;
     for (int k = 0; k < 3; ++k) {
         a.size[k] = p->size[k];
@@ -1071,6 +1124,17 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     if (p->kind == SANS_CORE_SHELL_CYLINDER) {
         a.cs_face = p->extra[0];
         a.fcs_face = (float)p->extra[0];
+    }
+    if (is_shape_independent(p->kind)) {
+        a.si_scale = (float)p->extra[0];
+        a.si_u = p->extra[1];
+        a.si_z = 1.0 / (1.0 + 2.0 * p->extra[1]);
+        if (p->kind == SANS_TEUBNER_STREY) {
+            const double k = 2.0 * 3.141592653589793 / p->size[1], ix2 = 1.0 / (p->size[0] * p->size[0]);
+            a.ts_c = (float)(ix2 - k * k);
+            a.ts_e = (float)(4.0 * k * k * ix2);
+            a.ts_n = (float)((k * k + ix2) * (k * k + ix2));
+        }
     }
     if (p->kind == SANS_POLYMER_MICELLE) {
         a.mic_n = (float)p->extra[0];

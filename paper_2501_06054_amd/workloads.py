@@ -29,6 +29,9 @@ KINDS = ("sphere", "core_shell", "cylinder", "ellipsoid", "parallelepiped")
 #: polymer micelle (Tables I-II)
 EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle", "hollow_cylinder",
                "core_shell_cylinder", "core_shell_ellipsoid", "hollow_prism_thick")
+#: shape-independent models: a cross-section in 1/cm, extra[0] = I(0)
+SHAPE_INDEPENDENT_KINDS = ("guinier", "ornstein_zernike", "dab", "gauss_coil", "poly_gauss_coil",
+                           "teubner_strey")
 ORIENT_KINDS = ("fixed", "gaussian", "isotropic", "uniform_angles")
 MODES = ("mc", "quad", "surrogate")
 POLY_KINDS = ("schulz", "gaussian")
@@ -220,6 +223,23 @@ def oriented_hollow_prism_thick() -> dict:
                               orient_sigma=(10 * DEG, 10 * DEG, 10 * DEG), nx=256, ny=256))
 
 
+def teubner_strey() -> dict:
+    """Microemulsion (Teubner-Strey): correlation length 60 A, period 150 A
+    (peak at q = 0.042 / A inside the cone), I(0) = 5 / cm, 256x256, 1e9
+    neutrons."""
+    return dict(name="teubner_strey", n=10**9, seed=17, exp_id=0,
+                params=params(kind="teubner_strey", size=(60.0, 150.0, 0.0), extra=(5.0, 0.0, 0.0, 0.0),
+                              nx=256, ny=256))
+
+
+def poly_gauss_coil() -> dict:
+    """Polymer coils with Schulz-Zimm masses (Mw/Mn = 2, z-average Rg = 60 A),
+    I(0) = 20 / cm, 256x256, 1e9 neutrons (the power in FP64)."""
+    return dict(name="poly_gauss_coil", n=10**9, seed=18, exp_id=0,
+                params=params(kind="poly_gauss_coil", size=(60.0, 0.0, 0.0), extra=(20.0, 1.0, 0.0, 0.0),
+                              nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -236,6 +256,8 @@ WORKLOADS = {
     "quad_hollow_cylinder": quad_hollow_cylinder,
     "iso_core_shell_ellipsoid": iso_core_shell_ellipsoid,
     "oriented_hollow_prism_thick": oriented_hollow_prism_thick,
+    "teubner_strey": teubner_strey,
+    "poly_gauss_coil": poly_gauss_coil,
 }
 
 

@@ -115,6 +115,12 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
     (dict(kind="hollow_prism_thick", size=(20.0, 30.0, 40.0), shell=10.0), "SANS_E_INVALID_ARG"),
     (dict(kind="hollow_prism_thick", size=(20.0, 30.0, 40.0), shell=2.0, poly=0.1, poly_mask=1),
      "SANS_E_UNSUPPORTED"),
+    (dict(kind="guinier", size=(20.0, 0.0, 0.0), extra=(-1.0, 0.0, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="teubner_strey", size=(20.0, 0.0, 0.0), extra=(1.0, 0.0, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="poly_gauss_coil", size=(20.0, 0.0, 0.0), extra=(1.0, -0.5, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="dab", size=(20.0, 0.0, 0.0), extra=(1.0, 0.0, 0.0, 0.0), poly=0.1), "SANS_E_UNSUPPORTED"),
+    (dict(kind="gauss_coil", size=(20.0, 0.0, 0.0), extra=(1.0, 0.0, 0.0, 0.0), sq_phi=0.1, sq_radius=30.0),
+     "SANS_E_UNSUPPORTED"),
 ])
 def test_capped_body_params_rejected_without_gpu(S, over, code):
     from paper_2501_06054_amd import workloads as W
@@ -126,6 +132,6 @@ def test_capped_body_params_rejected_without_gpu(S, over, code):
 def test_unknown_kind_rejected_without_gpu(S):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=1.0))
-    sp.kind = 13
+    sp.kind = 19
     h = C.c_void_p()
     assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED

@@ -139,10 +139,10 @@ def test_batch_gaussian_sizes(S):
 
 def test_batch_extra_models(S):
     """Barbells and capped cylinders (each experiment with its own cap rule),
-    hollow and core-shell bodies and polymer micelles mixed with the other
-    models: each equals its plain trace, and the extra models match the
-    oracle."""
-    exps = _small_batch(n_exp=14, n_lo=2e5, n_hi=5e5)
+    hollow and core-shell bodies, polymer micelles and shape-independent
+    models mixed with the other models: each equals its plain trace, and the
+    extra models match the oracle."""
+    exps = _small_batch(n_exp=17, n_lo=2e5, n_hi=5e5)
     caps = {1: dict(kind="barbell", size=(20.0, 300.0, 35.0), poly_mask=7, quad_n=40),
             4: dict(kind="capped_cylinder", size=(30.0, 120.0, 45.0), poly=0.1, poly_mask=7, quad_n=23),
             7: dict(kind="barbell", size=(15.0, 80.0, 15.0), poly_mask=7, quad_n=76),
@@ -154,7 +154,12 @@ def test_batch_extra_models(S):
                      sld=(1e-6, 4e-6, 6.3e-6), poly_mask=3),
             12: dict(kind="core_shell_ellipsoid", size=(20.0, 30.0, 70.0), shell=4.0,
                      sld=(1e-6, 4e-6, 6.3e-6), poly_mask=7),
-            13: dict(kind="hollow_prism_thick", size=(40.0, 60.0, 150.0), shell=5.0, poly_mask=0)}
+            13: dict(kind="hollow_prism_thick", size=(40.0, 60.0, 150.0), shell=5.0, poly_mask=0),
+            14: dict(kind="teubner_strey", size=(60.0, 150.0, 0.0), extra=(5.0, 0.0, 0.0, 0.0), poly=0.0,
+                     sq_phi=0.0),
+            15: dict(kind="poly_gauss_coil", size=(60.0, 0.0, 0.0), extra=(20.0, 1.0, 0.0, 0.0), poly=0.0,
+                     sq_phi=0.0),
+            16: dict(kind="guinier", size=(45.0, 0.0, 0.0), extra=(3.0, 0.0, 0.0, 0.0), poly=0.0, sq_phi=0.0)}
     for e, over in caps.items():
         exps[e]["params"] = dict(exps[e]["params"], **over)
     got = _run_batch(S, exps)
@@ -163,7 +168,7 @@ def test_batch_extra_models(S):
         ref = m.trace(x["n"], x["seed"], exp_id=e).cpu().numpy()
         m.close()
         assert np.allclose(got[e], ref, rtol=1e-9, atol=0), e
-    for e in (1, 4, 8, 9, 10, 11, 12, 13):
+    for e in (1, 4, 8, 9, 10, 11, 12, 13, 14, 15, 16):
         x = exps[e]
         ref = oracle.trace(x["params"], x["n"], x["seed"], exp_id=e, nthreads=NTHREADS)
         assert np.array_equal(got[e] != 0, ref != 0), e

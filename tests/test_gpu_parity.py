@@ -210,6 +210,17 @@ PER_NEUTRON = {
                                                  extra=(0.0, 0.0, 0.0, 0.0), sld=(6e-6, 1e-6, 3e-6),
                                                  poly=0.3, poly_kind="gaussian", poly_mask=1,
                                                  orient_mean=(0.7, 0.2, 0.0)), 30011),
+    # shape-independent models (cross-sections in 1/cm)
+    "guinier": (W.params(kind="guinier", size=(45, 0, 0), extra=(3.0, 0, 0, 0)), 30011),
+    "ornstein_zernike": (W.params(kind="ornstein_zernike", size=(80, 0, 0), extra=(3.0, 0, 0, 0)), 30011),
+    "dab": (W.params(kind="dab", size=(120, 0, 0), extra=(3.0, 0, 0, 0)), 30011),
+    "gauss_coil": (W.params(kind="gauss_coil", size=(70, 0, 0), extra=(3.0, 0, 0, 0)), 30011),
+    "poly_gauss_coil": (W.workload("poly_gauss_coil")["params"], 50021),
+    "poly_gauss_coil_broad": (W.params(kind="poly_gauss_coil", size=(150, 0, 0), extra=(1.0, 4.0, 0, 0)),
+                              30011),
+    "teubner_strey": (W.workload("teubner_strey")["params"], 50021),
+    "quad_teubner_strey": (W.params(kind="teubner_strey", mode="quad", size=(60, 150, 0),
+                                    extra=(5.0, 0, 0, 0)), 2003),
 }
 
 
@@ -235,7 +246,7 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "iso_parallelepiped", "poly_ellipsoid_py", "gauss_coreshell_py", "oriented_barbell",
              "poly_capped_cylinder_iso", "oriented_hollow_prism", "iso_poly_hollow_prism", "micelle_py",
              "oriented_core_shell_cylinder", "iso_poly_hollow_cylinder", "iso_core_shell_ellipsoid",
-             "oriented_hollow_prism_thick"]
+             "oriented_hollow_prism_thick", "teubner_strey", "poly_gauss_coil", "dab"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -368,7 +379,8 @@ def test_full_size_coreshell(S):
 
 
 @pytest.mark.parametrize("name", ["oriented_cylinder", "oriented_ellipsoid", "oriented_barbell",
-                                  "oriented_hollow_prism", "micelle_py", "oriented_core_shell_cylinder"])
+                                  "oriented_hollow_prism", "micelle_py", "oriented_core_shell_cylinder",
+                                  "teubner_strey"])
 def test_full_size_sampled(S, name):
     """1e9- and 1e8-neutron workloads: the full run equals the sum of its chunks, and
     windows spread over the whole index range match the oracle neutron by
