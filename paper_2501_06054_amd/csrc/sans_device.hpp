@@ -66,6 +66,7 @@ struct TraceArgs {
     double slit_w, slit_h, slit_z;
     double lambda0, lambda_span;  // lambda = lambda0 + lambda_span (2u - 1)
     double half_x, half_y, half_z;
+    double clear_x, clear_y;      // the half-widths less 1e-9 of themselves
     double omc;                   // 1 - cos(alpha)
     double det_z, det_hw, det_hh;
     double inv_px, inv_py;        // nx / det_w, ny / det_h
@@ -930,9 +931,26 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     const double lambda = __builtin_fma(a.lambda_span, 2.0 * u64(r1.x) - 1.0, a.lambda0);
     const double k = div_d(2.0 * kPi, lambda);
 
-    // slab entry/exit along src + s k, s >= 0
+    // slab entry/exit along src + s k, s >= 0.  The beam axis first: when
+    // the path between the two z faces stays clear of the x and y faces at
+    // both ends (by a margin of 1e-9 of the half-widths, far above the
+    // rounding of the crossing points), those faces cannot cut it, and the
+    // three-axis intersection below would select exactly the z crossings.
     double s_in = 0.0, s_out = 1e300;
-    {
+    bool clear = false;
+    if (kz != 0.0) {
+        const double inv = rcp_d(kz);
+        const double t1 = (-a.half_z - a.src_z) * inv, t2 = (a.half_z - a.src_z) * inv;
+        const double zin = fmax(0.0, fmin(t1, t2)), zout = fmax(t1, t2);
+        const double xa = __builtin_fma(zin, kx, sx), xb = __builtin_fma(zout, kx, sx);
+        const double ya = __builtin_fma(zin, ky, sy), yb = __builtin_fma(zout, ky, sy);
+        clear = fmax(fabs(xa), fabs(xb)) < a.clear_x && fmax(fabs(ya), fabs(yb)) < a.clear_y;
+        s_in = zin;
+        s_out = zout;
+    }
+    if (!clear) {
+        s_in = 0.0;
+        s_out = 1e300;
         const double o[3] = {sx, sy, a.src_z};
         const double dv[3] = {kx, ky, kz};
         const double h[3] = {a.half_x, a.half_y, a.half_z};
