@@ -52,7 +52,9 @@ typedef struct {
                               with I(0) = extra[0]): 13 Guinier, 14
                               Ornstein-Zernike, 15 Debye-Anderson-Brumberger,
                               16 Gaussian coil, 17 polydisperse Gaussian
-                              coil, 18 Teubner-Strey                         */
+                              coil, 18 Teubner-Strey, 19 power law, 20
+                              Gaussian peak, 21 Lorentzian peak, 22 mass
+                              fractal, 23 star polymer, 24 Gauss-Lorentz gel */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -569,7 +571,7 @@ static double micelle_f2(const double s[3], const double sld[3], const double ex
 
 /* Shape-independent models: the macroscopic cross-section dSigma/dOmega(q)
  * in 1/cm, scale = its value at q = 0 (extra[0]); the length is size[0]. */
-static int shape_independent(int kind) { return kind >= 13 && kind <= 18; }
+static int shape_independent(int kind) { return kind >= 13 && kind <= 24; }
 
 static double shape_independent_iq(const orc_params* p, const double s[3], double q)
 {
@@ -603,6 +605,34 @@ static double shape_independent_iq(const orc_params* p, const double s[3], doubl
         double a = (k * k + ixi2) * (k * k + ixi2);
         return scale * a / (a + 2.0 * (ixi2 - k * k) * q * q + q * q * q * q);
     }
+    case 19: /* power law scale q^-m, m = extra[1] (q in 1/A) */
+        return scale * pow(q, -p->extra[1]);
+    case 20: { /* Gaussian peak at q0 = extra[1], standard deviation extra[2] */
+        double d = (q - p->extra[1]) / p->extra[2];
+        return scale * exp(-0.5 * d * d);
+    }
+    case 21: { /* Lorentzian peak at q0 = extra[1], half width extra[2] */
+        double d = (q - p->extra[1]) / p->extra[2];
+        return scale / (1.0 + d * d);
+    }
+    case 22: { /* mass fractal of dimension D = extra[1] with cut-off length xi:
+                  the transform of r^(D - 3) exp(-r/xi), normalised at q = 0:
+                  sin((D - 1) atan(q xi)) / ((D - 1) q xi (1 + (q xi)^2)^((D - 1)/2)) */
+        double dm1 = p->extra[1] - 1.0, qx = q * l;
+        if (qx < 1e-6) return scale * (1.0 - (dm1 + 1.0) * (dm1 + 2.0) / 6.0 * qx * qx); /* Guinier term */
+        return scale * sin(dm1 * atan(qx)) / (dm1 * qx * pow(1.0 + qx * qx, 0.5 * dm1));
+    }
+    case 23: { /* star polymer of f = extra[1] Gaussian arms (Benoit), Rg of the
+                  star: pairs on one arm give the chain's double average, pairs
+                  on two arms the square of its single average, v = f (q Rg)^2 / (3f - 2) */
+        double f = p->extra[1];
+        double v = f * x / (3.0 * f - 2.0);
+        double a = chain_amplitude(v);
+        return scale * (debye_chain(v) + (f - 1.0) * a * a) / f;
+    }
+    case 24: /* Gauss-Lorentz gel: a Gaussian (length size[0], I(0) = extra[0]) plus
+                an Ornstein-Zernike term (length size[1], I(0) = extra[1]) */
+        return scale * exp(-0.5 * x) + p->extra[1] / (1.0 + q * s[1] * q * s[1]);
     }
     return 0.0;
 }

@@ -949,3 +949,80 @@ def test_shape_independent_weight_units(orc):
     omega = 2 * math.pi * (1 - math.cos(p["cone_alpha"]))
     assert hit.sum() > 1000
     assert np.allclose(ex[hit, 1], ex[hit, 10] * 100.0 * omega * 3.0, rtol=1e-12)
+
+
+def test_power_law_scale_invariance(orc):
+    # I(l q) = l^-m I(q), and I(1 / A) = scale
+    for m in (1.0, 2.5, 4.0):
+        p = W.params(kind="power_law", extra=(2.0, m, 0.0, 0.0))
+        for q, lam in ((0.003, 2.0), (0.02, 0.37), (0.05, 5.0)):
+            a = orc.form_f2(p, q, (q, 0.0, 0.0))
+            b = orc.form_f2(p, lam * q, (lam * q, 0.0, 0.0))
+            assert b == pytest.approx(a * lam ** (-m), rel=1e-13)
+        assert orc.form_f2(p, 1.0, (1.0, 0.0, 0.0)) == pytest.approx(2.0, rel=1e-15)
+
+
+def test_peaks_widths_and_areas(orc):
+    from scipy import integrate
+    q0, w = 0.03, 0.004
+    g = W.params(kind="gaussian_peak", extra=(2.0, q0, w, 0.0))
+    lz = W.params(kind="lorentz_peak", extra=(2.0, q0, w, 0.0))
+    fg = lambda q: orc.form_f2(g, q, (q, 0.0, 0.0))
+    fl = lambda q: orc.form_f2(lz, q, (q, 0.0, 0.0))
+    # heights at the centre and one width away; symmetry
+    assert fg(q0) == pytest.approx(2.0, rel=1e-15)
+    assert fg(q0 + w) == pytest.approx(2.0 * math.exp(-0.5), rel=1e-13)
+    assert fl(q0 - w) == pytest.approx(1.0, rel=1e-13)
+    for d in (0.001, 0.0067):
+        assert fg(q0 + d) == pytest.approx(fg(q0 - d), rel=1e-12)
+        assert fl(q0 + d) == pytest.approx(fl(q0 - d), rel=1e-12)
+    # areas: 2 sqrt(2 pi) w and 2 (2 w atan(L / w)) over [q0 - L, q0 + L]
+    L = 20 * w
+    ag, _ = integrate.quad(fg, q0 - L, q0 + L, epsabs=0, epsrel=1e-12, limit=200)
+    al, _ = integrate.quad(fl, q0 - L, q0 + L, epsabs=0, epsrel=1e-12, limit=200)
+    assert ag == pytest.approx(2.0 * math.sqrt(2 * math.pi) * w, rel=1e-10)
+    assert al == pytest.approx(2.0 * 2 * w * math.atan(L / w), rel=1e-10)
+
+
+@pytest.mark.parametrize("D", [1.5, 2.2, 2.8])
+@pytest.mark.parametrize("q", [0.0, 1e-4, 0.01, 0.05, 0.2])
+def test_mass_fractal_is_the_transform_of_its_correlation(orc, D, q):
+    # gamma(r) = r^(D - 3) exp(-r / xi): int r^(D-1) exp(-r/xi) sin(qr)/(qr) dr by quad
+    # with the algebraic weight r^(D-1)
+    from scipy import integrate
+    xi = 80.0
+    f = lambda r: math.exp(-r / xi) * (math.sin(q * r) / (q * r) if q * r > 0 else 1.0)
+    num, _ = integrate.quad(f, 0.0, 80 * xi, weight="alg", wvar=(D - 1.0, 0.0), limit=2000,
+                            epsabs=0.0, epsrel=1e-11)
+    den, _ = integrate.quad(lambda r: math.exp(-r / xi), 0.0, 80 * xi, weight="alg",
+                            wvar=(D - 1.0, 0.0), limit=2000, epsabs=0.0, epsrel=1e-11)
+    p = W.params(kind="mass_fractal", size=(xi, 0.0, 0.0), extra=(3.0, D, 0.0, 0.0))
+    assert orc.form_f2(p, q, (0.0, 0.0, q)) == pytest.approx(3.0 * num / den, rel=2e-9)
+
+
+@pytest.mark.parametrize("f", [1.0, 2.0, 3.0, 6.0, 12.0])
+@pytest.mark.parametrize("q", [0.0, 0.004, 0.02, 0.08])
+def test_star_polymer_arm_averages(orc, f, q):
+    """f arms of equal length, Rg^2 of the star = (3f - 2)/f times the arm's
+    N b^2/6: pairs on one arm give the chain double average, on two arms the
+    product of two single averages; a two-arm star is a linear chain."""
+    rg = 50.0
+    v = f * (q * rg) ** 2 / (3 * f - 2)
+    ref = (f * _chain_double_average(v) + f * (f - 1) * _chain_single_average(v) ** 2) / (f * f)
+    p = W.params(kind="star_polymer", size=(rg, 0.0, 0.0), extra=(1.5, f, 0.0, 0.0))
+    assert orc.form_f2(p, q, (q, 0.0, 0.0)) == pytest.approx(1.5 * ref, rel=1e-11)
+    if f == 2.0:
+        lin = W.params(kind="gauss_coil", size=(rg, 0.0, 0.0), extra=(1.5, 0.0, 0.0, 0.0))
+        assert orc.form_f2(p, q, (q, 0.0, 0.0)) == pytest.approx(orc.form_f2(lin, q, (q, 0.0, 0.0)), rel=1e-12)
+
+
+@pytest.mark.parametrize("q", [0.0, 0.003, 0.02, 0.07])
+def test_gauss_lorentz_gel_is_two_transforms(orc, q):
+    # a Gaussian correlation exp(-r^2 / (2 a^2)) and an Ornstein-Zernike one
+    a, xi = 30.0, 90.0
+    tg = _radial_transform(lambda r: np.exp(-r * r / (2 * a * a)), q, 12 * a)
+    tg0 = _radial_transform(lambda r: np.exp(-r * r / (2 * a * a)), 0.0, 12 * a)
+    tl = _radial_transform(lambda r: np.exp(-r / xi) / r, q, 60 * xi, n=16000)
+    tl0 = _radial_transform(lambda r: np.exp(-r / xi) / r, 0.0, 60 * xi, n=16000)
+    p = W.params(kind="gauss_lorentz_gel", size=(a, xi, 0.0), extra=(2.0, 0.7, 0.0, 0.0))
+    assert orc.form_f2(p, q, (q, 0.0, 0.0)) == pytest.approx(2.0 * tg / tg0 + 0.7 * tl / tl0, rel=1e-8)
