@@ -95,7 +95,8 @@ typedef enum {
                                   cavity whose edges are 2 shell shorter
                                   (0 < 2 shell < every edge; monodisperse)      */
     /* Shape-independent models (Tables I-II): the weight is the macroscopic
-     * cross-section dSigma/dOmega(q) in 1/cm, extra[0] its value at q = 0,
+     * cross-section dSigma/dOmega(q) in 1/cm, extra[0] its value at q = 0
+     * (unless stated otherwise),
      * L = size[0] (phi, poly and the structure factor unused: poly > 0 or
      * sq_phi > 0 is SANS_E_UNSUPPORTED). */
     SANS_GUINIER = 13,           /* exp(-(q L)^2 / 3), L the radius of gyration */
@@ -104,8 +105,19 @@ typedef enum {
     SANS_GAUSS_COIL = 16,        /* Debye function of (q L)^2, L the coil's Rg  */
     SANS_POLY_GAUSS_COIL = 17,   /* coils with Schulz-Zimm masses, U = Mw/Mn - 1
                                     = extra[1] in [0, 100], L the z-average Rg  */
-    SANS_TEUBNER_STREY = 18      /* microemulsion: correlation length L, period
+    SANS_TEUBNER_STREY = 18,     /* microemulsion: correlation length L, period
                                     size[1]                                    */
+    SANS_POWER_LAW = 19,         /* extra[0] q^-m, m = extra[1] in [0, 10]
+                                    (q in 1/A; no length)                      */
+    SANS_GAUSSIAN_PEAK = 20,     /* exp(-(q - q0)^2/(2 w^2)), q0 = extra[1],
+                                    w = extra[2] > 0; extra[0] at q0            */
+    SANS_LORENTZ_PEAK = 21,      /* 1/(1 + ((q - q0)/w)^2), q0, w as above      */
+    SANS_MASS_FRACTAL = 22,      /* the transform of r^(D-3) exp(-r/L), D =
+                                    extra[1] in (1, 3]                         */
+    SANS_STAR_POLYMER = 23,      /* f = extra[1] >= 1 Gaussian arms, L the star's
+                                    radius of gyration                         */
+    SANS_GAUSS_LORENTZ_GEL = 24  /* extra[0] exp(-(q L)^2/2) + extra[1] /
+                                    (1 + (q size[1])^2)                        */
 } sans_kind;
 
 /* How the particle size and orientation enter the weight. */

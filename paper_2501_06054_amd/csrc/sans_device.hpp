@@ -111,6 +111,10 @@ struct TraceArgs {
     float si_scale;
     double si_u, si_z;
     float ts_c, ts_e, ts_n;
+    // further model constants: power law m; peaks q0, 1/width; mass fractal
+    // D - 1, D (D + 1)/6; star f/(3f - 2), f - 1, 1/f; gel Lorentz scale and
+    // length
+    double si_a, si_b, si_c;
     // core-shell cylinder: thickness of the shell on each end face (A)
     double cs_face;
     float fcs_face;
@@ -460,11 +464,12 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kBarbell = 5, kCappedCylinder = 6, kHollowPrism = 7, kMicelle = 8,
               kHollowCylinder = 9, kCoreShellCylinder = 10, kCoreShellEllipsoid = 11,
               kHollowPrismThick = 12, kGuinier = 13, kOrnsteinZernike = 14, kDab = 15, kGaussCoil = 16,
-              kPolyGaussCoil = 17, kTeubnerStrey = 18 };
+              kPolyGaussCoil = 17, kTeubnerStrey = 18, kPowerLaw = 19, kGaussianPeak = 20,
+              kLorentzPeak = 21, kMassFractal = 22, kStarPolymer = 23, kGaussLorentzGel = 24 };
 
 // Shape-independent models: the weight is a cross-section in 1/cm of |Q|.
 template <int KIND>
-constexpr bool kShapeIndependent = KIND >= kGuinier && KIND <= kTeubnerStrey;
+constexpr bool kShapeIndependent = KIND >= kGuinier && KIND <= kGaussLorentzGel;
 
 // Orientation enters the weight (the particles from the cylinder on; the
 // micelle and the shape-independent models are isotropic).
@@ -621,9 +626,33 @@ __device__ __forceinline__ float shape_iq(const TraceArgs& a, double len, double
             f = 2.0 * (expm1(-z) + z) / (z * z);
         }
         return a.si_scale * (float)f;
-    } else {
+    } else if constexpr (KIND == kTeubnerStrey) {
         const float d = (float)(q * q) + a.ts_c;
         return a.si_scale * a.ts_n * rcpf(__builtin_fmaf(d, d, a.ts_e));
+    } else if constexpr (KIND == kPowerLaw) {
+        // in FP64: the few smallest-q neutrons carry the total, and an FP32
+        // exponent of magnitude m |log2 q| would cost them about 1e-6
+        return a.si_scale * (float)exp2(-a.si_a * log2(q));
+    } else if constexpr (KIND == kGaussianPeak) {
+        const float d = (float)((q - a.si_a) * a.si_b);
+        return a.si_scale * __expf(-0.5f * d * d);
+    } else if constexpr (KIND == kLorentzPeak) {
+        const float d = (float)((q - a.si_a) * a.si_b);
+        return a.si_scale * rcpf(__builtin_fmaf(d, d, 1.0f));
+    } else if constexpr (KIND == kMassFractal) {
+        // sin((D - 1) atan(q xi)) / ((D - 1) q xi (1 + (q xi)^2)^((D - 1)/2)),
+        // its Guinier term below q xi = 1e-3
+        if (ql < 1e-3f) return a.si_scale * __builtin_fmaf(-(float)a.si_b, x, 1.0f);
+        const float dm1 = (float)a.si_a;
+        return a.si_scale * sinf(dm1 * atanf(ql)) * rcpf(dm1 * ql * exp2f(0.5f * dm1 * log2f(1.0f + x)));
+    } else if constexpr (KIND == kStarPolymer) {
+        float pc, psi;
+        chain_functions(x * (float)a.si_a, pc, psi);
+        return a.si_scale * (float)a.si_c * __builtin_fmaf((float)a.si_b * psi, psi, pc);
+    } else {
+        // Gauss-Lorentz gel: exp(-(q L)^2 / 2) plus an Ornstein-Zernike term
+        const float q2 = (float)(q * a.si_b);
+        return __builtin_fmaf(a.si_scale, __expf(-0.5f * x), (float)a.si_a * rcpf(__builtin_fmaf(q2, q2, 1.0f)));
     }
 }
 

@@ -261,7 +261,8 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
         const int k[3] = {b0 ? 1 : 0, b1 ? 1 : 0, b2 ? 1 : 0};
         return c43 * expand_moment(f, k, poly_kind, poly);
     }
-    case 13: case 14: case 15: case 16: case 17: case 18:
+    case 13: case 14: case 15: case 16: case 17: case 18: case 19: case 20: case 21: case 22: case 23:
+    case 24:
         return 1.0;  // shape-independent: no particles (the weight uses the cross-section)
     case 12: {
         // the box minus its cavity (monodisperse)

@@ -512,7 +512,13 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 15: batch_tile<15>(a, tl.first, tl.count, hist, tab); break;
         case 16: batch_tile<16>(a, tl.first, tl.count, hist, tab); break;
         case 17: batch_tile<17>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<18>(a, tl.first, tl.count, hist, tab); break;
+        case 18: batch_tile<18>(a, tl.first, tl.count, hist, tab); break;
+        case 19: batch_tile<19>(a, tl.first, tl.count, hist, tab); break;
+        case 20: batch_tile<20>(a, tl.first, tl.count, hist, tab); break;
+        case 21: batch_tile<21>(a, tl.first, tl.count, hist, tab); break;
+        case 22: batch_tile<22>(a, tl.first, tl.count, hist, tab); break;
+        case 23: batch_tile<23>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<24>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -764,6 +770,12 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(16)
         SANS_CASE(17)
         SANS_CASE(18)
+        SANS_CASE(19)
+        SANS_CASE(20)
+        SANS_CASE(21)
+        SANS_CASE(22)
+        SANS_CASE(23)
+        SANS_CASE(24)
     }
 #undef SANS_CASE
     return nullptr;
@@ -797,6 +809,12 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(16)
         SANS_CASE(17)
         SANS_CASE(18)
+        SANS_CASE(19)
+        SANS_CASE(20)
+        SANS_CASE(21)
+        SANS_CASE(22)
+        SANS_CASE(23)
+        SANS_CASE(24)
     }
 #undef SANS_CASE
     return nullptr;
@@ -827,6 +845,12 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(16)
         SANS_CASE(17)
         SANS_CASE(18)
+        SANS_CASE(19)
+        SANS_CASE(20)
+        SANS_CASE(21)
+        SANS_CASE(22)
+        SANS_CASE(23)
+        SANS_CASE(24)
     }
 #undef SANS_CASE
     return nullptr;
@@ -857,6 +881,12 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(16)
         SANS_CASE(17)
         SANS_CASE(18)
+        SANS_CASE(19)
+        SANS_CASE(20)
+        SANS_CASE(21)
+        SANS_CASE(22)
+        SANS_CASE(23)
+        SANS_CASE(24)
     }
 #undef SANS_CASE
     return nullptr;
@@ -884,6 +914,12 @@ PqFn pick_pq(int kind)
     case 16: return k_pq_avg<16>;
     case 17: return k_pq_avg<17>;
     case 18: return k_pq_avg<18>;
+    case 19: return k_pq_avg<19>;
+    case 20: return k_pq_avg<20>;
+    case 21: return k_pq_avg<21>;
+    case 22: return k_pq_avg<22>;
+    case 23: return k_pq_avg<23>;
+    case 24: return k_pq_avg<24>;
     }
     return nullptr;
 }
@@ -928,7 +964,7 @@ namespace {
 bool finite(double x) { return std::isfinite(x); }
 
 // Shape-independent models: a cross-section in 1/cm of |Q| only.
-bool is_shape_independent(int kind) { return kind >= SANS_GUINIER && kind <= SANS_TEUBNER_STREY; }
+bool is_shape_independent(int kind) { return kind >= SANS_GUINIER && kind <= SANS_GAUSS_LORENTZ_GEL; }
 
 // Orientation enters the weight (the micelle and the shape-independent
 // models are isotropic).
@@ -941,7 +977,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 18) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 24) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -956,8 +992,11 @@ int validate(const sans_params* p)
     if (p->tally < 0 || p->tally > 4) return fail(SANS_E_UNSUPPORTED, "unknown tally strategy");
     const bool two_sizes = p->kind == SANS_CYLINDER || p->kind == SANS_POLYMER_MICELLE
                            || p->kind == SANS_HOLLOW_CYLINDER || p->kind == SANS_CORE_SHELL_CYLINDER;
-    const int nsize = (p->kind <= 1 || (is_shape_independent(p->kind) && p->kind != SANS_TEUBNER_STREY))
-                          ? 1 : (two_sizes || p->kind == SANS_TEUBNER_STREY ? 2 : 3);
+    int nsize = p->kind <= 1 ? 1 : (two_sizes ? 2 : 3);
+    if (is_shape_independent(p->kind))
+        nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK) ? 0
+              : (p->kind == SANS_TEUBNER_STREY || p->kind == SANS_GAUSS_LORENTZ_GEL)                      ? 2
+                                                                                                            : 1;
     for (int k = 0; k < nsize; ++k)
         if (!(p->size[k] > 0.0) || !finite(p->size[k])) return fail(SANS_E_INVALID_ARG, "size must be > 0");
     if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
@@ -989,6 +1028,17 @@ int validate(const sans_params* p)
             return fail(SANS_E_INVALID_ARG, "shape-independent model: scale extra[0] must be >= 0");
         if (p->kind == SANS_POLY_GAUSS_COIL && !(p->extra[1] >= 0.0 && p->extra[1] <= 100.0))
             return fail(SANS_E_INVALID_ARG, "polydisperse coil: U = Mw/Mn - 1 (extra[1]) must be in [0, 100]");
+        if (p->kind == SANS_POWER_LAW && !(p->extra[1] >= 0.0 && p->extra[1] <= 10.0))
+            return fail(SANS_E_INVALID_ARG, "power law: exponent extra[1] must be in [0, 10]");
+        if ((p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK)
+            && !(p->extra[1] >= 0.0 && finite(p->extra[1]) && p->extra[2] > 0.0 && finite(p->extra[2])))
+            return fail(SANS_E_INVALID_ARG, "peak: need position extra[1] >= 0 and width extra[2] > 0");
+        if (p->kind == SANS_MASS_FRACTAL && !(p->extra[1] > 1.0 && p->extra[1] <= 3.0))
+            return fail(SANS_E_INVALID_ARG, "mass fractal: dimension extra[1] must be in (1, 3]");
+        if (p->kind == SANS_STAR_POLYMER && !(p->extra[1] >= 1.0 && finite(p->extra[1])))
+            return fail(SANS_E_INVALID_ARG, "star polymer: arm number extra[1] must be >= 1");
+        if (p->kind == SANS_GAUSS_LORENTZ_GEL && !(p->extra[1] >= 0.0 && finite(p->extra[1])))
+            return fail(SANS_E_INVALID_ARG, "gel: Lorentzian scale extra[1] must be >= 0");
         if (p->poly > 0.0) return fail(SANS_E_UNSUPPORTED, "shape-independent model: no size distribution");
         if (p->sq_phi > 0.0) return fail(SANS_E_UNSUPPORTED, "shape-independent model: no structure factor");
     }
@@ -1131,6 +1181,16 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
         a.si_scale = (float)p->extra[0];
         a.si_u = p->extra[1];
         a.si_z = 1.0 / (1.0 + 2.0 * p->extra[1]);
+        const double e1 = p->extra[1], e2 = p->extra[2];
+        switch (p->kind) {
+        case SANS_POWER_LAW: a.si_a = e1; break;
+        case SANS_GAUSSIAN_PEAK:
+        case SANS_LORENTZ_PEAK: a.si_a = e1; a.si_b = 1.0 / e2; break;
+        case SANS_MASS_FRACTAL: a.si_a = e1 - 1.0; a.si_b = e1 * (e1 + 1.0) / 6.0; break;
+        case SANS_STAR_POLYMER: a.si_a = e1 / (3.0 * e1 - 2.0); a.si_b = e1 - 1.0; a.si_c = 1.0 / e1; break;
+        case SANS_GAUSS_LORENTZ_GEL: a.si_a = e1; a.si_b = p->size[1]; break;
+        default: break;
+        }
         if (p->kind == SANS_TEUBNER_STREY) {
             const double k = 2.0 * 3.141592653589793 / p->size[1], ix2 = 1.0 / (p->size[0] * p->size[0]);
             a.ts_c = (float)(ix2 - k * k);

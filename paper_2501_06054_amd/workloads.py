@@ -31,7 +31,8 @@ EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle", "hollow_
                "core_shell_cylinder", "core_shell_ellipsoid", "hollow_prism_thick")
 #: shape-independent models: a cross-section in 1/cm, extra[0] = I(0)
 SHAPE_INDEPENDENT_KINDS = ("guinier", "ornstein_zernike", "dab", "gauss_coil", "poly_gauss_coil",
-                           "teubner_strey")
+                           "teubner_strey", "power_law", "gaussian_peak", "lorentz_peak", "mass_fractal",
+                           "star_polymer", "gauss_lorentz_gel")
 ORIENT_KINDS = ("fixed", "gaussian", "isotropic", "uniform_angles")
 MODES = ("mc", "quad", "surrogate")
 POLY_KINDS = ("schulz", "gaussian")
@@ -240,6 +241,14 @@ def poly_gauss_coil() -> dict:
                               nx=256, ny=256))
 
 
+def mass_fractal() -> dict:
+    """Mass fractal aggregates, dimension 2.3, cut-off length 300 A, I(0) =
+    50 / cm, 256x256, 1e9 neutrons."""
+    return dict(name="mass_fractal", n=10**9, seed=19, exp_id=0,
+                params=params(kind="mass_fractal", size=(300.0, 0.0, 0.0), extra=(50.0, 2.3, 0.0, 0.0),
+                              nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -258,6 +267,7 @@ WORKLOADS = {
     "oriented_hollow_prism_thick": oriented_hollow_prism_thick,
     "teubner_strey": teubner_strey,
     "poly_gauss_coil": poly_gauss_coil,
+    "mass_fractal": mass_fractal,
 }
 
 

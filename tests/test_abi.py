@@ -121,6 +121,12 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
     (dict(kind="dab", size=(20.0, 0.0, 0.0), extra=(1.0, 0.0, 0.0, 0.0), poly=0.1), "SANS_E_UNSUPPORTED"),
     (dict(kind="gauss_coil", size=(20.0, 0.0, 0.0), extra=(1.0, 0.0, 0.0, 0.0), sq_phi=0.1, sq_radius=30.0),
      "SANS_E_UNSUPPORTED"),
+    (dict(kind="power_law", extra=(1.0, 11.0, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="gaussian_peak", extra=(1.0, 0.03, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="lorentz_peak", extra=(1.0, -0.01, 0.01, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="mass_fractal", size=(100.0, 0.0, 0.0), extra=(1.0, 1.0, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="star_polymer", size=(100.0, 0.0, 0.0), extra=(1.0, 0.5, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="gauss_lorentz_gel", size=(100.0, 0.0, 0.0), extra=(1.0, 1.0, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
 ])
 def test_capped_body_params_rejected_without_gpu(S, over, code):
     from paper_2501_06054_amd import workloads as W
@@ -132,6 +138,6 @@ def test_capped_body_params_rejected_without_gpu(S, over, code):
 def test_unknown_kind_rejected_without_gpu(S):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=1.0))
-    sp.kind = 19
+    sp.kind = 25
     h = C.c_void_p()
     assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED

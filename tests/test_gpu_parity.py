@@ -221,6 +221,13 @@ PER_NEUTRON = {
     "teubner_strey": (W.workload("teubner_strey")["params"], 50021),
     "quad_teubner_strey": (W.params(kind="teubner_strey", mode="quad", size=(60, 150, 0),
                                     extra=(5.0, 0, 0, 0)), 2003),
+    "power_law": (W.params(kind="power_law", extra=(1e-4, 3.2, 0, 0)), 30011),
+    "gaussian_peak": (W.params(kind="gaussian_peak", extra=(4.0, 0.03, 0.004, 0)), 30011),
+    "lorentz_peak": (W.params(kind="lorentz_peak", extra=(4.0, 0.025, 0.006, 0)), 30011),
+    "mass_fractal": (W.workload("mass_fractal")["params"], 50021),
+    "mass_fractal_thin": (W.params(kind="mass_fractal", size=(40, 0, 0), extra=(2.0, 1.4, 0, 0)), 30011),
+    "star_polymer": (W.params(kind="star_polymer", size=(70, 0, 0), extra=(3.0, 6.0, 0, 0)), 30011),
+    "gauss_lorentz_gel": (W.params(kind="gauss_lorentz_gel", size=(25, 120, 0), extra=(2.0, 0.8, 0, 0)), 30011),
 }
 
 
@@ -246,7 +253,8 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "iso_parallelepiped", "poly_ellipsoid_py", "gauss_coreshell_py", "oriented_barbell",
              "poly_capped_cylinder_iso", "oriented_hollow_prism", "iso_poly_hollow_prism", "micelle_py",
              "oriented_core_shell_cylinder", "iso_poly_hollow_cylinder", "iso_core_shell_ellipsoid",
-             "oriented_hollow_prism_thick", "teubner_strey", "poly_gauss_coil", "dab"]
+             "oriented_hollow_prism_thick", "teubner_strey", "poly_gauss_coil", "dab", "mass_fractal",
+             "star_polymer", "gaussian_peak"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
