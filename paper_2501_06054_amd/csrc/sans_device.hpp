@@ -280,6 +280,21 @@ __device__ __forceinline__ float sph3j_f(float x)
     return 3.0f * __builtin_fmaf(-x, c, s) * (ix * ix * ix);
 }
 
+// 3 j1(x)/x from its Taylor series to x^30, given x^2, for x <= kSphLongMax:
+// no branch and no square root.  FP32 Horner: absolute error below 1.4e-6
+// there (1 at x = 0), set by the cancellation of the alternating terms.
+constexpr float kSphLongMax = 8.0f;
+template <int M>
+__device__ __forceinline__ float sph_horner(float x2, float r)
+{
+    if constexpr (M < 0) {
+        return r;
+    } else {
+        return sph_horner<M - 1>(x2, __builtin_fmaf(r, x2, SphC<M>::v));
+    }
+}
+__device__ __forceinline__ float sph3j_long(float x2) { return sph_horner<14>(x2, SphC<15>::v); }
+
 // 2 J1(x)/x (the cylinder's cross-section factor, Eq. (9)): Taylor series
 // below 3, the device library's j1f above.
 __device__ __forceinline__ float lambda1_f(float x)
@@ -856,10 +871,30 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
             }
             avg = i0 == 0 ? f2 : 0.0f;
         } else if (a.quad_dims == 1) {
+            bool done = false;
+            if constexpr (KIND == kEllipsoid) {
+                // spheroid (a = b): x^2 = (q a sin)^2 + (q c mu)^2; when every
+                // lane's x stays within the long series' range, no branch
+                const float qa = q * s[0], qc = q * s[2];
+                if (__all(fmaxf(qa, qc) <= kSphLongMax)) {
+                    float sum = 0.0f;
 #pragma unroll 4
-            for (int i = i0; i < n; i += istep) {
-                const float f = amplitude_f<KIND>(a, s, q, q * stt[i], 0.0f, q * mu[i], y);
-                avg = __builtin_fmaf(wmu[i], f * f, avg);
+                    for (int i = i0; i < n; i += istep) {
+                        const float xa = qa * stt[i], xc = qc * mu[i];
+                        const float p = sph3j_long(__builtin_fmaf(xa, xa, xc * xc));
+                        sum = __builtin_fmaf(wmu[i], p * p, sum);
+                    }
+                    const float f0 = a.contrast * (float)(4.0 / 3.0 * kPi) * s[0] * s[1] * s[2];
+                    avg = f0 * f0 * sum;
+                    done = true;
+                }
+            }
+            if (!done) {
+#pragma unroll 4
+                for (int i = i0; i < n; i += istep) {
+                    const float f = amplitude_f<KIND>(a, s, q, q * stt[i], 0.0f, q * mu[i], y);
+                    avg = __builtin_fmaf(wmu[i], f * f, avg);
+                }
             }
         } else if constexpr (KIND == kParallelepiped) {
             const float f0 = a.contrast * s[0] * s[1] * s[2];
