@@ -54,7 +54,12 @@ typedef struct {
                               16 Gaussian coil, 17 polydisperse Gaussian
                               coil, 18 Teubner-Strey, 19 power law, 20
                               Gaussian peak, 21 Lorentzian peak, 22 mass
-                              fractal, 23 star polymer, 24 Gauss-Lorentz gel */
+                              fractal, 23 star polymer, 24 Gauss-Lorentz gel;
+                              isotropic particles: 25 fuzzy sphere, 26
+                              vesicle, 27 multilayer vesicle, 28 linear
+                              pearls; shape-independent: 29 surface fractal,
+                              30 two power law, 31 Guinier-Porod, 32
+                              spinodal                                      */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -571,7 +576,7 @@ static double micelle_f2(const double s[3], const double sld[3], const double ex
 
 /* Shape-independent models: the macroscopic cross-section dSigma/dOmega(q)
  * in 1/cm, scale = its value at q = 0 (extra[0]); the length is size[0]. */
-static int shape_independent(int kind) { return kind >= 13 && kind <= 24; }
+static int shape_independent(int kind) { return (kind >= 13 && kind <= 24) || (kind >= 29 && kind <= 32); }
 
 static double shape_independent_iq(const orc_params* p, const double s[3], double q)
 {
@@ -633,6 +638,77 @@ static double shape_independent_iq(const orc_params* p, const double s[3], doubl
     case 24: /* Gauss-Lorentz gel: a Gaussian (length size[0], I(0) = extra[0]) plus
                 an Ornstein-Zernike term (length size[1], I(0) = extra[1]) */
         return scale * exp(-0.5 * x) + p->extra[1] / (1.0 + q * s[1] * q * s[1]);
+    case 29: { /* surface fractal of dimension Ds = extra[1] in (2, 3): the
+                  transform of r^(3 - Ds) exp(-r/xi), a = 5 - Ds, normalised at 0:
+                  sin(a atan(q xi)) / (a q xi (1 + (q xi)^2)^(a/2)) */
+        double am = 5.0 - p->extra[1], qx = q * l;
+        if (qx < 1e-6) return scale * (1.0 - am * (am + 1.0) / 6.0 * qx * qx);
+        return scale * sin(am * atan(qx)) / (am * qx * pow(1.0 + qx * qx, 0.5 * am));
+    }
+    case 30: { /* two power laws joined at qc = extra[2]: A q^-m1 below, the
+                  continuous A qc^(m2 - m1) q^-m2 above; A = extra[0], m1 =
+                  extra[1], m2 = extra[3] */
+        double qc = p->extra[2];
+        if (q <= qc) return scale * pow(q, -p->extra[1]);
+        return scale * pow(qc, p->extra[3] - p->extra[1]) * pow(q, -p->extra[3]);
+    }
+    case 31: { /* Guinier-Porod (Hammouda): G q^-s exp(-(q Rg)^2/(3 - s)) up to q1,
+                  D q^-m beyond, with q1 and D fixed by the continuity of the
+                  intensity and of its slope; G = extra[0], s = extra[1], m = extra[2] */
+        double sd = p->extra[1], m = p->extra[2];
+        double q1 = sqrt((m - sd) * (3.0 - sd) / 2.0) / l;
+        if (q <= q1) return scale * pow(q, -sd) * exp(-x / (3.0 - sd));
+        double d = scale * exp(-(m - sd) / 2.0) * pow(q1, m - sd);
+        return d * pow(q, -m);
+    }
+    case 32: { /* spinodal decomposition (Furukawa's scaling form): peak I_max =
+                  extra[0] at q_max = extra[1], exponent gamma = extra[2]:
+                  (1 + g/2) x^2 / (g/2 + x^(2 + g)), x = q / q_max */
+        double g = p->extra[2], xx = q / p->extra[1];
+        return scale * (1.0 + 0.5 * g) * xx * xx / (0.5 * g + pow(xx, 2.0 + g));
+    }
+    }
+    return 0.0;
+}
+
+/* Isotropic sphere-based particles (Tables I-II, group F), their squared
+ * amplitude averaged over orientations:
+ * fuzzy sphere: the sphere convolved with a Gaussian of width sigma = shell
+ *   (its amplitude times exp(-(q sigma)^2 / 2));
+ * vesicle: a solvent-filled shell, bore R = size[0], thickness shell;
+ * multilayer vesicle: n = extra[0] shells of thickness shell, separated by
+ *   solvent layers of size[1], the first around a solvent core of radius R;
+ * linear pearls: n = extra[0] spheres of radius R in a straight line with
+ *   gaps size[1] between them, orientation averaged (Debye's pair sum). */
+static double sphere_family_f2(const orc_params* p, const double s[3], double q)
+{
+    double drho = p->sld[0] - p->sld[2], sh = p->sld[1] - p->sld[2];
+    switch (p->kind) {
+    case 25: {
+        double f = drho * vol_sphere(s[0]) * orc_sph(q * s[0]) * exp(-0.5 * q * q * p->shell * p->shell);
+        return f * f;
+    }
+    case 26: {
+        double ri = s[0], ro = s[0] + p->shell;
+        double f = sh * (vol_sphere(ro) * orc_sph(q * ro) - vol_sphere(ri) * orc_sph(q * ri));
+        return f * f;
+    }
+    case 27: {
+        int n = (int)p->extra[0];
+        double f = 0.0;
+        for (int k = 0; k < n; ++k) {
+            double ri = s[0] + k * (p->shell + s[1]), ro = ri + p->shell;
+            f += sh * (vol_sphere(ro) * orc_sph(q * ro) - vol_sphere(ri) * orc_sph(q * ri));
+        }
+        return f * f;
+    }
+    case 28: {
+        int n = (int)p->extra[0];
+        double f = drho * vol_sphere(s[0]) * orc_sph(q * s[0]);
+        double d = 2.0 * s[0] + s[1], pairs = n;
+        for (int k = 1; k < n; ++k) pairs += 2.0 * (n - k) * orc_sinc(q * k * d);
+        return f * f * pairs;
+    }
     }
     return 0.0;
 }
@@ -644,6 +720,7 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
 {
     if (shape_independent(p->kind)) return shape_independent_iq(p, s, q);
     if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
+    if (p->kind >= 25 && p->kind <= 28) return sphere_family_f2(p, s, q);
     double f = amplitude(p->kind, s, p->shell, p->sld, p->extra, q, qa, qb, qc, p->quad_n);
     return f * f;
 }
@@ -738,6 +815,23 @@ double orc_mean_volume(const orc_params* p)
     case 6: /* all three sizes scale together (or none): V(y) = V(1) y^3 */
         return (ORC_PI * s[0] * s[0] * s[1] + caps_volume(s, p->kind == 5))
              * size_moment(p, p->poly_mask == 7 ? 3 : 0);
+    case 25: /* fuzzy sphere: the sphere's volume */
+        return vol_sphere(s[0]) * size_moment(p, b0 ? 3 : 0);
+    case 26: { /* vesicle: the shell, 4/3 pi ((R y + t)^3 - (R y)^3) */
+        double al[3] = {s[0], s[0], s[0]}, be[3] = {p->shell, p->shell, p->shell}, z[3] = {0.0, 0.0, 0.0};
+        int bb[3] = {b0, b0, b0};
+        return 4.0 / 3.0 * ORC_PI * (prod_moment(p, al, be, bb, 3) - prod_moment(p, al, z, bb, 3));
+    }
+    case 27: { /* multilayer vesicle: the n shells (monodisperse) */
+        double v = 0.0;
+        for (int k = 0; k < (int)p->extra[0]; ++k) {
+            double ri = s[0] + k * (p->shell + s[1]);
+            v += vol_sphere(ri + p->shell) - vol_sphere(ri);
+        }
+        return v;
+    }
+    case 28: /* linear pearls: n spheres */
+        return p->extra[0] * vol_sphere(s[0]) * size_moment(p, b0 ? 3 : 0);
     case 8: /* N chains, each a core block and a corona chain */
         return p->extra[0] * (p->extra[1] + p->extra[2]);
     case 9: { /* pi L ((R + t)^2 - R^2) = pi (L y^b1)(2 R t y^b0 + t^2) */

@@ -1026,3 +1026,126 @@ def test_gauss_lorentz_gel_is_two_transforms(orc, q):
     tl0 = _radial_transform(lambda r: np.exp(-r / xi) / r, 0.0, 60 * xi, n=16000)
     p = W.params(kind="gauss_lorentz_gel", size=(a, xi, 0.0), extra=(2.0, 0.7, 0.0, 0.0))
     assert orc.form_f2(p, q, (q, 0.0, 0.0)) == pytest.approx(2.0 * tg / tg0 + 0.7 * tl / tl0, rel=1e-8)
+
+
+# ------------------------------------------------------------------ sphere family, more shape-independent models
+
+def _fuzzy_ball_density(r, R, sig):
+    """The ball indicator convolved with an isotropic Gaussian of width sig."""
+    from scipy.special import erf
+    a = (R - r) / (math.sqrt(2) * sig)
+    b = (R + r) / (math.sqrt(2) * sig)
+    g = sig / (r * math.sqrt(2 * math.pi)) * (np.exp(-0.5 * ((r - R) / sig) ** 2) - np.exp(-0.5 * ((r + R) / sig) ** 2))
+    return 0.5 * (erf(a) + erf(b)) - g
+
+
+@pytest.mark.parametrize("q", [0.0, 0.01, 0.04, 0.12])
+def test_fuzzy_sphere_is_the_smeared_ball(orc, q):
+    R, sig = 50.0, 6.0
+    rho = lambda r: _fuzzy_ball_density(np.maximum(r, 1e-9), R, sig)
+    # the smeared ball keeps the ball's volume
+    assert _radial_transform(rho, 0.0, R + 12 * sig, n=8000) == pytest.approx(4 / 3 * math.pi * R ** 3, rel=1e-9)
+    f = _radial_transform(rho, q, R + 12 * sig, n=8000)
+    p = W.params(kind="fuzzy_sphere", size=(R, 0, 0), shell=sig, sld=(1.0, 0.0, 0.0))
+    assert orc.form_f2(p, q, (q, 0.0, 0.0)) == pytest.approx(f * f, rel=1e-9, abs=1e-12 * (R ** 3) ** 2)
+
+
+def test_vesicle_is_a_solvent_filled_shell(orc):
+    # the core-shell sphere whose core is solvent; its volume is the shell's
+    ves = W.params(kind="vesicle", size=(60.0, 0, 0), shell=8.0, sld=(0.0, 1e-6, 6.3e-6))
+    cs = W.params(kind="core_shell", size=(60.0, 0, 0), shell=8.0, sld=(6.3e-6, 1e-6, 6.3e-6))
+    for q in (0.0, 0.007, 0.03, 0.09):
+        assert orc.form_f2(ves, q, (q, 0, 0)) == pytest.approx(orc.amplitude(cs, q, (q, 0, 0)) ** 2, rel=1e-12)
+    assert orc.mean_volume(ves) == pytest.approx(4 / 3 * math.pi * (68.0 ** 3 - 60.0 ** 3), rel=1e-13)
+
+
+@pytest.mark.parametrize("q", [0.0, 0.005, 0.02, 0.06])
+def test_multilayer_vesicle_is_its_layers(orc, q):
+    """n shells of thickness t, water layers w, around a solvent core of radius
+    R: the radial transform of the piecewise-constant contrast; one shell is the
+    vesicle."""
+    R, t, w, n = 40.0, 5.0, 12.0, 4
+    edges = [(R + k * (t + w), R + k * (t + w) + t) for k in range(n)]
+    rho = lambda r: sum(((r >= a) & (r < b)).astype(float) for a, b in edges)
+    f = sum(_radial_transform(lambda r: np.ones_like(r), q, b, n=4000)
+            - _radial_transform(lambda r: np.ones_like(r), q, a, n=4000) for a, b in edges)
+    p = W.params(kind="multilayer_vesicle", size=(R, w, 0), shell=t, sld=(0.0, 1.0, 0.0),
+                 extra=(float(n), 0, 0, 0))
+    assert orc.form_f2(p, q, (0, q, 0)) == pytest.approx(f * f, rel=1e-9)
+    one = dict(p, extra=(1.0, 0, 0, 0))
+    ves = W.params(kind="vesicle", size=(R, 0, 0), shell=t, sld=(0.0, 1.0, 0.0))
+    assert orc.form_f2(one, q, (0, q, 0)) == pytest.approx(orc.form_f2(ves, q, (0, q, 0)), rel=1e-13)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5])
+@pytest.mark.parametrize("q", [0.0, 0.004, 0.02, 0.07])
+def test_linear_pearls_orientation_average(orc, n, q):
+    """|sum_k exp(i Q.r_k)|^2 averaged over the string's orientations (Gauss
+    rule in mu = cos angle) times the sphere's F^2."""
+    R, gap = 20.0, 15.0
+    d = 2 * R + gap
+    z = (np.arange(n) - 0.5 * (n - 1)) * d
+    mu, wm = np.polynomial.legendre.leggauss(200)
+    phase = q * mu[:, None] * z[None, :]
+    amp2 = np.cos(phase).sum(1) ** 2 + np.sin(phase).sum(1) ** 2
+    avg = 0.5 * np.sum(wm * amp2)
+    sph = W.params(kind="sphere", size=(R, 0, 0), sld=(1e-6, 0, 0))
+    p = W.params(kind="linear_pearls", size=(R, gap, 0), sld=(1e-6, 0, 0), extra=(float(n), 0, 0, 0))
+    ref = orc.amplitude(sph, q, (q, 0, 0)) ** 2 * avg
+    assert orc.form_f2(p, q, (q, 0, 0)) == pytest.approx(ref, rel=1e-10)
+    assert orc.mean_volume(p) == pytest.approx(n * 4 / 3 * math.pi * R ** 3, rel=1e-13)
+
+
+@pytest.mark.parametrize("ds", [2.1, 2.5, 2.9])
+@pytest.mark.parametrize("q", [0.0, 1e-4, 0.01, 0.05])
+def test_surface_fractal_is_the_transform_of_its_correlation(orc, ds, q):
+    from scipy import integrate
+    xi = 150.0
+    f = lambda r: math.exp(-r / xi) * (math.sin(q * r) / (q * r) if q * r > 0 else 1.0)
+    num, _ = integrate.quad(f, 0.0, 80 * xi, weight="alg", wvar=(5.0 - ds, 0.0), limit=2000,
+                            epsabs=0.0, epsrel=1e-11)
+    den, _ = integrate.quad(lambda r: math.exp(-r / xi), 0.0, 80 * xi, weight="alg",
+                            wvar=(5.0 - ds, 0.0), limit=2000, epsabs=0.0, epsrel=1e-11)
+    p = W.params(kind="surface_fractal", size=(xi, 0, 0), extra=(2.0, ds, 0, 0))
+    assert orc.form_f2(p, q, (q, 0, 0)) == pytest.approx(2.0 * num / den, rel=2e-9)
+
+
+def test_two_power_law_continuity_and_slopes(orc):
+    p = W.params(kind="two_power_law", extra=(3e-5, 1.5, 0.02, 4.0))
+    f = lambda q: orc.form_f2(p, q, (q, 0, 0))
+    qc = 0.02
+    assert f(qc * (1 + 1e-12)) == pytest.approx(f(qc), rel=1e-10)
+    for q, lam in ((0.002, 3.0), (0.03, 1.7)):
+        m = 1.5 if q * lam <= qc else 4.0
+        assert f(lam * q) == pytest.approx(f(q) * lam ** (-m), rel=1e-12)
+    assert f(1e-3) == pytest.approx(3e-5 * 1e-3 ** -1.5, rel=1e-13)
+
+
+@pytest.mark.parametrize("sd,m", [(0.0, 4.0), (1.0, 3.5), (2.0, 4.0)])
+def test_guinier_porod_is_smooth_at_the_join(orc, sd, m):
+    """The Guinier and Porod pieces meet with equal values and equal log-log
+    slopes; below the join the slope is -s - 2 (q Rg)^2/(3 - s)."""
+    rg = 60.0
+    p = W.params(kind="guinier_porod", size=(rg, 0, 0), extra=(7.0, sd, m, 0))
+    f = lambda q: orc.form_f2(p, q, (q, 0, 0))
+    q1 = math.sqrt((m - sd) * (3 - sd) / 2) / rg
+    h = 1e-7 * q1
+    lo, hi = f(q1 - h), f(q1 + h)
+    assert hi == pytest.approx(lo, rel=1e-6)
+    slope = lambda q: (math.log(f(q * (1 + 1e-6))) - math.log(f(q * (1 - 1e-6)))) / 2e-6
+    assert slope(q1 * (1 - 1e-4)) == pytest.approx(slope(q1 * (1 + 1e-4)), abs=2e-3)
+    assert slope(q1 * (1 + 1e-3)) == pytest.approx(-m, abs=1e-6)
+    q = 0.3 * q1
+    assert slope(q) == pytest.approx(-sd - 2 * (q * rg) ** 2 / (3 - sd), rel=1e-6)
+
+
+@pytest.mark.parametrize("g", [1.0, 3.0, 4.0])
+def test_spinodal_peak(orc, g):
+    qm = 0.02
+    p = W.params(kind="spinodal", extra=(9.0, qm, g, 0))
+    f = lambda q: orc.form_f2(p, q, (q, 0, 0))
+    assert f(qm) == pytest.approx(9.0, rel=1e-14)
+    assert f(qm * (1 + 1e-4)) < f(qm) and f(qm * (1 - 1e-4)) < f(qm)
+    # q^2 at small q, q^-g at large q
+    assert f(2e-6) / f(1e-6) == pytest.approx(4.0, rel=1e-6)
+    assert f(200 * qm) / f(100 * qm) == pytest.approx(2.0 ** (-g), rel=1e-3)
