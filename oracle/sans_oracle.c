@@ -642,7 +642,7 @@ static double shape_independent_iq(const orc_params* p, const double s[3], doubl
                   transform of r^(3 - Ds) exp(-r/xi), a = 5 - Ds, normalised at 0:
                   sin(a atan(q xi)) / (a q xi (1 + (q xi)^2)^(a/2)) */
         double am = 5.0 - p->extra[1], qx = q * l;
-        if (qx < 1e-6) return scale * (1.0 - am * (am + 1.0) / 6.0 * qx * qx);
+        if (qx < 1e-6) return scale * (1.0 - (am + 1.0) * (am + 2.0) / 6.0 * qx * qx); /* Guinier term */
         return scale * sin(am * atan(qx)) / (am * qx * pow(1.0 + qx * qx, 0.5 * am));
     }
     case 30: { /* two power laws joined at qc = extra[2]: A q^-m1 below, the

@@ -1149,3 +1149,15 @@ def test_spinodal_peak(orc, g):
     # q^2 at small q, q^-g at large q
     assert f(2e-6) / f(1e-6) == pytest.approx(4.0, rel=1e-6)
     assert f(200 * qm) / f(100 * qm) == pytest.approx(2.0 ** (-g), rel=1e-3)
+
+
+@pytest.mark.parametrize("kind,dim", [("mass_fractal", 2.3), ("surface_fractal", 2.4)])
+def test_fractal_guinier_terms(orc, kind, dim):
+    """Across the switch to the small-argument series the fractal models stay
+    continuous: sin(a atan x)/(a x (1 + x^2)^(a/2)) = 1 - (a + 1)(a + 2) x^2/6 + O(x^4)."""
+    xi = 1e6
+    p = W.params(kind=kind, size=(xi, 0, 0), extra=(1.0, dim, 0, 0))
+    a = dim - 1.0 if kind == "mass_fractal" else 5.0 - dim
+    for x in (0.9e-6, 1.1e-6, 3e-5):
+        q = x / xi
+        assert 1.0 - orc.form_f2(p, q, (q, 0, 0)) == pytest.approx((a + 1) * (a + 2) * x * x / 6, rel=1e-4)
