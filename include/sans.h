@@ -116,8 +116,27 @@ typedef enum {
                                     extra[1] in (1, 3]                         */
     SANS_STAR_POLYMER = 23,      /* f = extra[1] >= 1 Gaussian arms, L the star's
                                     radius of gyration                         */
-    SANS_GAUSS_LORENTZ_GEL = 24  /* extra[0] exp(-(q L)^2/2) + extra[1] /
+    SANS_GAUSS_LORENTZ_GEL = 24, /* extra[0] exp(-(q L)^2/2) + extra[1] /
                                     (1 + (q size[1])^2)                        */
+    /* Isotropic sphere-based particles (Tables I-II, group F); R = size[0]. */
+    SANS_FUZZY_SPHERE = 25,      /* sphere smeared by a Gaussian of width shell */
+    SANS_VESICLE = 26,           /* solvent-filled shell of thickness shell > 0
+                                    around a bore of radius R; sld[1] the
+                                    shell, sld[2] the solvent inside and out;
+                                    the particle volume is the shell's         */
+    SANS_MULTILAYER_VESICLE = 27,/* extra[0] (integer) such shells, a solvent
+                                    layer size[1] between them; monodisperse   */
+    SANS_LINEAR_PEARLS = 28,     /* extra[0] (integer) spheres of radius R in a
+                                    line, gaps size[1]; orientation averaged   */
+    /* More shape-independent models (cross-sections in 1/cm, as above). */
+    SANS_SURFACE_FRACTAL = 29,   /* transform of r^(3-Ds) exp(-r/L), Ds =
+                                    extra[1] in (2, 3]                         */
+    SANS_TWO_POWER_LAW = 30,     /* extra[0] q^-m1 up to qc, continued as q^-m2;
+                                    m1 = extra[1], qc = extra[2], m2 = extra[3] */
+    SANS_GUINIER_POROD = 31,     /* Guinier (dimension s = extra[1], Rg = L)
+                                    joined smoothly to Porod q^-m, m = extra[2] */
+    SANS_SPINODAL = 32           /* Furukawa: peak extra[0] at q_max = extra[1],
+                                    exponent gamma = extra[2]                  */
 } sans_kind;
 
 /* How the particle size and orientation enter the weight. */

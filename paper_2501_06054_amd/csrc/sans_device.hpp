@@ -114,7 +114,11 @@ struct TraceArgs {
     // further model constants: power law m; peaks q0, 1/width; mass fractal
     // D - 1, D (D + 1)/6; star f/(3f - 2), f - 1, 1/f; gel Lorentz scale and
     // length
-    double si_a, si_b, si_c;
+    double si_a, si_b, si_c, si_d, si_e;
+    // sphere family: shells or pearls (n), the step between shells or the gap
+    // between pearls (A)
+    int32_t sf_n;
+    double sf_gap;
     // core-shell cylinder: thickness of the shell on each end face (A)
     double cs_face;
     float fcs_face;
@@ -480,16 +484,23 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kHollowCylinder = 9, kCoreShellCylinder = 10, kCoreShellEllipsoid = 11,
               kHollowPrismThick = 12, kGuinier = 13, kOrnsteinZernike = 14, kDab = 15, kGaussCoil = 16,
               kPolyGaussCoil = 17, kTeubnerStrey = 18, kPowerLaw = 19, kGaussianPeak = 20,
-              kLorentzPeak = 21, kMassFractal = 22, kStarPolymer = 23, kGaussLorentzGel = 24 };
+              kLorentzPeak = 21, kMassFractal = 22, kStarPolymer = 23, kGaussLorentzGel = 24,
+              kFuzzySphere = 25, kVesicle = 26, kMultilayerVesicle = 27, kLinearPearls = 28,
+              kSurfaceFractal = 29, kTwoPowerLaw = 30, kGuinierPorod = 31, kSpinodal = 32 };
 
 // Shape-independent models: the weight is a cross-section in 1/cm of |Q|.
 template <int KIND>
-constexpr bool kShapeIndependent = KIND >= kGuinier && KIND <= kGaussLorentzGel;
+constexpr bool kShapeIndependent = (KIND >= kGuinier && KIND <= kGaussLorentzGel)
+                                   || (KIND >= kSurfaceFractal && KIND <= kSpinodal);
 
-// Orientation enters the weight (the particles from the cylinder on; the
-// micelle and the shape-independent models are isotropic).
+// Isotropic sphere-based particles (fuzzy sphere, vesicles, pearl strings).
 template <int KIND>
-constexpr bool kAniso = KIND >= kCylinder && KIND != kMicelle && !kShapeIndependent<KIND>;
+constexpr bool kSphereFamily = KIND >= kFuzzySphere && KIND <= kLinearPearls;
+
+// Orientation enters the weight (the particles from the cylinder to the
+// thick hollow prism, but the micelle).
+template <int KIND>
+constexpr bool kAniso = KIND >= kCylinder && KIND <= kHollowPrismThick && KIND != kMicelle;
 
 // Bodies of revolution about C: cylinders (plain, hollow, core-shell),
 // barbell, capped cylinder (only the axis projection Q.C and Q_AB enter, the
@@ -654,9 +665,9 @@ __device__ __forceinline__ float shape_iq(const TraceArgs& a, double len, double
     } else if constexpr (KIND == kLorentzPeak) {
         const float d = (float)((q - a.si_a) * a.si_b);
         return a.si_scale * rcpf(__builtin_fmaf(d, d, 1.0f));
-    } else if constexpr (KIND == kMassFractal) {
-        // sin((D - 1) atan(q xi)) / ((D - 1) q xi (1 + (q xi)^2)^((D - 1)/2)),
-        // its Guinier term below q xi = 1e-3
+    } else if constexpr (KIND == kMassFractal || KIND == kSurfaceFractal) {
+        // sin(a atan(q xi)) / (a q xi (1 + (q xi)^2)^(a/2)), a = D - 1 (mass)
+        // or 5 - Ds (surface), its Guinier term below q xi = 1e-3
         if (ql < 1e-3f) return a.si_scale * __builtin_fmaf(-(float)a.si_b, x, 1.0f);
         const float dm1 = (float)a.si_a;
         return a.si_scale * sinf(dm1 * atanf(ql)) * rcpf(dm1 * ql * exp2f(0.5f * dm1 * log2f(1.0f + x)));
@@ -664,10 +675,60 @@ __device__ __forceinline__ float shape_iq(const TraceArgs& a, double len, double
         float pc, psi;
         chain_functions(x * (float)a.si_a, pc, psi);
         return a.si_scale * (float)a.si_c * __builtin_fmaf((float)a.si_b * psi, psi, pc);
-    } else {
+    } else if constexpr (KIND == kGaussLorentzGel) {
         // Gauss-Lorentz gel: exp(-(q L)^2 / 2) plus an Ornstein-Zernike term
         const float q2 = (float)(q * a.si_b);
         return __builtin_fmaf(a.si_scale, __expf(-0.5f * x), (float)a.si_a * rcpf(__builtin_fmaf(q2, q2, 1.0f)));
+    } else if constexpr (KIND == kTwoPowerLaw) {
+        // q^-m1 up to qc, qc^(m2 - m1) q^-m2 beyond (FP64 powers)
+        const double v = q <= a.si_b ? exp2(-a.si_a * log2(q)) : a.si_d * exp2(-a.si_c * log2(q));
+        return a.si_scale * (float)v;
+    } else if constexpr (KIND == kGuinierPorod) {
+        // q^-s exp(-(q Rg)^2 / (3 - s)) up to q1, (D/G) q^-m beyond
+        if (q <= a.si_c) return a.si_scale * (float)exp2(-a.si_a * log2(q)) * __expf(-x * (float)a.si_e);
+        return a.si_scale * (float)(a.si_d * exp2(-a.si_b * log2(q)));
+    } else {
+        // spinodal: (1 + g/2) x^2 / (g/2 + x^(2 + g)), x = q / q_max (FP64 power)
+        const double xs = q * a.si_a;
+        const double v = a.si_c * xs * xs / (0.5 * a.si_b + exp2((2.0 + a.si_b) * log2(xs)));
+        return a.si_scale * (float)v;
+    }
+}
+
+// Isotropic sphere-based particles (Tables I-II, group F), F^2 averaged over
+// orientations; R the (drawn) sphere or bore radius, the phases in FP64:
+// fuzzy sphere: the sphere smeared by a Gaussian of width shell, its
+// amplitude times exp(-(q shell)^2 / 2); vesicle: a solvent-filled shell of
+// thickness shell; multilayer vesicle: n such shells, one every shell + gap;
+// linear pearls: n spheres in a line, centre spacing 2R + gap, with the
+// orientation average sum_jk sinc(q r_jk) of the pair phases.
+template <int KIND>
+__device__ __forceinline__ float sphere_family_f2(const TraceArgs& a, double R, double q)
+{
+    constexpr float k43pi = (float)(4.0 / 3.0 * kPi);
+    if constexpr (KIND == kFuzzySphere) {
+        const float r = (float)R, qs = (float)(q * a.shell);
+        const float f = a.contrast * k43pi * r * r * r * sph3j_d(q * R) * __expf(-0.5f * qs * qs);
+        return f * f;
+    } else if constexpr (KIND == kVesicle || KIND == kMultilayerVesicle) {
+        const int n = KIND == kVesicle ? 1 : a.sf_n;
+        float f = 0.0f;
+        double ri = R;
+        for (int k = 0; k < n; ++k) {
+            const double ro = ri + a.shell;
+            const float fi = (float)ri, fo = (float)ro;
+            f += fo * fo * fo * sph3j_d(q * ro) - fi * fi * fi * sph3j_d(q * ri);
+            ri = ro + a.sf_gap;
+        }
+        f *= a.cs_shell * k43pi;
+        return f * f;
+    } else {
+        const float r = (float)R;
+        const float fs = a.contrast * k43pi * r * r * r * sph3j_d(q * R);
+        const double d = __builtin_fma(2.0, R, a.sf_gap);
+        float pairs = (float)a.sf_n;
+        for (int k = 1; k < a.sf_n; ++k) pairs += 2.0f * (float)(a.sf_n - k) * sinc_d(q * (k * d));
+        return fs * fs * pairs;
     }
 }
 
@@ -865,6 +926,8 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
                 f2 = micelle_f2(a, s[0], s[1], (double)q);
             } else if constexpr (kShapeIndependent<KIND>) {
                 f2 = shape_iq<KIND>(a, a.size[0], (double)q);
+            } else if constexpr (kSphereFamily<KIND>) {
+                f2 = sphere_family_f2<KIND>(a, s[0], (double)q);
             } else {
                 const float f = amplitude_f<KIND>(a, s, q, qa0, qb0, qc0, y);
                 f2 = f * f;
@@ -1109,6 +1172,8 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
                             (a.poly_mask & 2) ? a.size[1] * y : a.size[1], qd);
         } else if constexpr (kShapeIndependent<KIND>) {
             f2 = shape_iq<KIND>(a, a.size[0], qd);
+        } else if constexpr (kSphereFamily<KIND>) {
+            f2 = sphere_family_f2<KIND>(a, (a.poly_mask & 1) ? a.size[0] * y : a.size[0], qd);
         } else {
             const float f = amplitude_mc<KIND>(a, y, qd, qa, qb, qc);
             f2 = f * f;

@@ -261,8 +261,30 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
         const int k[3] = {b0 ? 1 : 0, b1 ? 1 : 0, b2 ? 1 : 0};
         return c43 * expand_moment(f, k, poly_kind, poly);
     }
+    case 25:
+    case 28:
+        // fuzzy sphere: the sphere; linear pearls: n spheres
+        return (kind == 28 ? extra[0] : 1.0) * c43 * size[0] * size[0] * size[0]
+             * size_moment(poly_kind, poly, b0 ? 3 : 0);
+    case 26: {
+        // the shell (R y + t)^3 - (R y)^3 = 3 R^2 t y^2 + 3 R t^2 y + t^3
+        const double r = size[0], t = shell;
+        if (!b0) return c43 * ((r + t) * (r + t) * (r + t) - r * r * r);
+        return c43 * (3.0 * r * r * t * size_moment(poly_kind, poly, 2) + 3.0 * r * t * t * size_moment(poly_kind, poly, 1)
+                      + t * t * t);
+    }
+    case 27: {
+        // n shells, one every shell + gap (monodisperse)
+        double v = 0.0, ri = size[0];
+        for (int k = 0; k < (int)extra[0]; ++k) {
+            const double ro = ri + shell;
+            v += c43 * (ro * ro * ro - ri * ri * ri);
+            ri = ro + size[1];
+        }
+        return v;
+    }
     case 13: case 14: case 15: case 16: case 17: case 18: case 19: case 20: case 21: case 22: case 23:
-    case 24:
+    case 24: case 29: case 30: case 31: case 32:
         return 1.0;  // shape-independent: no particles (the weight uses the cross-section)
     case 12: {
         // the box minus its cavity (monodisperse)

@@ -518,7 +518,15 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 21: batch_tile<21>(a, tl.first, tl.count, hist, tab); break;
         case 22: batch_tile<22>(a, tl.first, tl.count, hist, tab); break;
         case 23: batch_tile<23>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<24>(a, tl.first, tl.count, hist, tab); break;
+        case 24: batch_tile<24>(a, tl.first, tl.count, hist, tab); break;
+        case 25: batch_tile<25>(a, tl.first, tl.count, hist, tab); break;
+        case 26: batch_tile<26>(a, tl.first, tl.count, hist, tab); break;
+        case 27: batch_tile<27>(a, tl.first, tl.count, hist, tab); break;
+        case 28: batch_tile<28>(a, tl.first, tl.count, hist, tab); break;
+        case 29: batch_tile<29>(a, tl.first, tl.count, hist, tab); break;
+        case 30: batch_tile<30>(a, tl.first, tl.count, hist, tab); break;
+        case 31: batch_tile<31>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<32>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -776,6 +784,14 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(22)
         SANS_CASE(23)
         SANS_CASE(24)
+        SANS_CASE(25)
+        SANS_CASE(26)
+        SANS_CASE(27)
+        SANS_CASE(28)
+        SANS_CASE(29)
+        SANS_CASE(30)
+        SANS_CASE(31)
+        SANS_CASE(32)
     }
 #undef SANS_CASE
     return nullptr;
@@ -815,6 +831,14 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(22)
         SANS_CASE(23)
         SANS_CASE(24)
+        SANS_CASE(25)
+        SANS_CASE(26)
+        SANS_CASE(27)
+        SANS_CASE(28)
+        SANS_CASE(29)
+        SANS_CASE(30)
+        SANS_CASE(31)
+        SANS_CASE(32)
     }
 #undef SANS_CASE
     return nullptr;
@@ -851,6 +875,14 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(22)
         SANS_CASE(23)
         SANS_CASE(24)
+        SANS_CASE(25)
+        SANS_CASE(26)
+        SANS_CASE(27)
+        SANS_CASE(28)
+        SANS_CASE(29)
+        SANS_CASE(30)
+        SANS_CASE(31)
+        SANS_CASE(32)
     }
 #undef SANS_CASE
     return nullptr;
@@ -887,6 +919,14 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(22)
         SANS_CASE(23)
         SANS_CASE(24)
+        SANS_CASE(25)
+        SANS_CASE(26)
+        SANS_CASE(27)
+        SANS_CASE(28)
+        SANS_CASE(29)
+        SANS_CASE(30)
+        SANS_CASE(31)
+        SANS_CASE(32)
     }
 #undef SANS_CASE
     return nullptr;
@@ -920,6 +960,14 @@ PqFn pick_pq(int kind)
     case 22: return k_pq_avg<22>;
     case 23: return k_pq_avg<23>;
     case 24: return k_pq_avg<24>;
+    case 25: return k_pq_avg<25>;
+    case 26: return k_pq_avg<26>;
+    case 27: return k_pq_avg<27>;
+    case 28: return k_pq_avg<28>;
+    case 29: return k_pq_avg<29>;
+    case 30: return k_pq_avg<30>;
+    case 31: return k_pq_avg<31>;
+    case 32: return k_pq_avg<32>;
     }
     return nullptr;
 }
@@ -964,20 +1012,27 @@ namespace {
 bool finite(double x) { return std::isfinite(x); }
 
 // Shape-independent models: a cross-section in 1/cm of |Q| only.
-bool is_shape_independent(int kind) { return kind >= SANS_GUINIER && kind <= SANS_GAUSS_LORENTZ_GEL; }
+bool is_shape_independent(int kind)
+{
+    return (kind >= SANS_GUINIER && kind <= SANS_GAUSS_LORENTZ_GEL)
+           || (kind >= SANS_SURFACE_FRACTAL && kind <= SANS_SPINODAL);
+}
 
-// Orientation enters the weight (the micelle and the shape-independent
-// models are isotropic).
+// Isotropic sphere-based particles.
+bool is_sphere_family(int kind) { return kind >= SANS_FUZZY_SPHERE && kind <= SANS_LINEAR_PEARLS; }
+
+// Orientation enters the weight (the particles from the cylinder to the thick
+// hollow prism, but the micelle).
 bool is_aniso(int kind)
 {
-    return kind >= SANS_CYLINDER && kind != SANS_POLYMER_MICELLE && !is_shape_independent(kind);
+    return kind >= SANS_CYLINDER && kind <= SANS_HOLLOW_PRISM_THICK && kind != SANS_POLYMER_MICELLE;
 }
 
 int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 24) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 32) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -994,9 +1049,12 @@ int validate(const sans_params* p)
                            || p->kind == SANS_HOLLOW_CYLINDER || p->kind == SANS_CORE_SHELL_CYLINDER;
     int nsize = p->kind <= 1 ? 1 : (two_sizes ? 2 : 3);
     if (is_shape_independent(p->kind))
-        nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK) ? 0
-              : (p->kind == SANS_TEUBNER_STREY || p->kind == SANS_GAUSS_LORENTZ_GEL)                      ? 2
-                                                                                                            : 1;
+        nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK
+                 || p->kind == SANS_TWO_POWER_LAW || p->kind == SANS_SPINODAL)
+                    ? 0
+                : (p->kind == SANS_TEUBNER_STREY || p->kind == SANS_GAUSS_LORENTZ_GEL) ? 2
+                                                                                       : 1;
+    if (is_sphere_family(p->kind)) nsize = 1;
     for (int k = 0; k < nsize; ++k)
         if (!(p->size[k] > 0.0) || !finite(p->size[k])) return fail(SANS_E_INVALID_ARG, "size must be > 0");
     if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
@@ -1039,8 +1097,32 @@ int validate(const sans_params* p)
             return fail(SANS_E_INVALID_ARG, "star polymer: arm number extra[1] must be >= 1");
         if (p->kind == SANS_GAUSS_LORENTZ_GEL && !(p->extra[1] >= 0.0 && finite(p->extra[1])))
             return fail(SANS_E_INVALID_ARG, "gel: Lorentzian scale extra[1] must be >= 0");
+        if (p->kind == SANS_SURFACE_FRACTAL && !(p->extra[1] > 2.0 && p->extra[1] <= 3.0))
+            return fail(SANS_E_INVALID_ARG, "surface fractal: dimension extra[1] must be in (2, 3]");
+        if (p->kind == SANS_TWO_POWER_LAW
+            && !(p->extra[1] >= 0.0 && p->extra[1] <= 10.0 && p->extra[3] >= 0.0 && p->extra[3] <= 10.0
+                 && p->extra[2] > 0.0 && finite(p->extra[2])))
+            return fail(SANS_E_INVALID_ARG, "two power law: exponents in [0, 10], crossover extra[2] > 0");
+        if (p->kind == SANS_GUINIER_POROD
+            && !(p->extra[1] >= 0.0 && p->extra[1] < 3.0 && p->extra[2] > p->extra[1] && p->extra[2] <= 10.0))
+            return fail(SANS_E_INVALID_ARG, "Guinier-Porod: need 0 <= s = extra[1] < 3 and s < m = extra[2] <= 10");
+        if (p->kind == SANS_SPINODAL
+            && !(p->extra[1] > 0.0 && finite(p->extra[1]) && p->extra[2] > 0.0 && p->extra[2] <= 10.0))
+            return fail(SANS_E_INVALID_ARG, "spinodal: need q_max = extra[1] > 0 and 0 < gamma = extra[2] <= 10");
         if (p->poly > 0.0) return fail(SANS_E_UNSUPPORTED, "shape-independent model: no size distribution");
         if (p->sq_phi > 0.0) return fail(SANS_E_UNSUPPORTED, "shape-independent model: no structure factor");
+    }
+    if (is_sphere_family(p->kind)) {
+        if (p->kind == SANS_FUZZY_SPHERE && !(p->shell >= 0.0 && finite(p->shell)))
+            return fail(SANS_E_INVALID_ARG, "fuzzy sphere: the fuzz width (shell) must be >= 0");
+        if ((p->kind == SANS_VESICLE || p->kind == SANS_MULTILAYER_VESICLE) && !(p->shell > 0.0 && finite(p->shell)))
+            return fail(SANS_E_INVALID_ARG, "vesicle: the shell thickness must be > 0");
+        if ((p->kind == SANS_MULTILAYER_VESICLE || p->kind == SANS_LINEAR_PEARLS)
+            && !(p->size[1] >= 0.0 && finite(p->size[1]) && p->extra[0] >= 1.0 && p->extra[0] <= 1000.0
+                 && p->extra[0] == std::floor(p->extra[0])))
+            return fail(SANS_E_INVALID_ARG, "need a gap size[1] >= 0 and an integer count extra[0] in 1..1000");
+        if (p->kind == SANS_MULTILAYER_VESICLE && p->poly > 0.0 && p->poly_mask != 0)
+            return fail(SANS_E_UNSUPPORTED, "multilayer vesicle: monodisperse only");
     }
     if (p->kind == SANS_POLYMER_MICELLE) {
         if (!(p->extra[0] >= 1.0 && finite(p->extra[0])))
@@ -1173,6 +1255,10 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     }
     a.shell = p->shell;
     a.fshell = (float)p->shell;
+    if (is_sphere_family(p->kind)) {
+        a.sf_n = (int32_t)p->extra[0];
+        a.sf_gap = p->size[1];
+    }
     if (p->kind == SANS_CORE_SHELL_CYLINDER) {
         a.cs_face = p->extra[0];
         a.fcs_face = (float)p->extra[0];
@@ -1189,6 +1275,26 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
         case SANS_MASS_FRACTAL: a.si_a = e1 - 1.0; a.si_b = e1 * (e1 + 1.0) / 6.0; break;
         case SANS_STAR_POLYMER: a.si_a = e1 / (3.0 * e1 - 2.0); a.si_b = e1 - 1.0; a.si_c = 1.0 / e1; break;
         case SANS_GAUSS_LORENTZ_GEL: a.si_a = e1; a.si_b = p->size[1]; break;
+        case SANS_SURFACE_FRACTAL:
+            a.si_a = 5.0 - e1;
+            a.si_b = (6.0 - e1) * (7.0 - e1) / 6.0;
+            break;
+        case SANS_TWO_POWER_LAW:
+            a.si_a = e1;
+            a.si_b = e2;
+            a.si_c = p->extra[3];
+            a.si_d = std::pow(e2, p->extra[3] - e1);
+            break;
+        case SANS_GUINIER_POROD: {
+            const double q1 = std::sqrt((e2 - e1) * (3.0 - e1) / 2.0) / p->size[0];
+            a.si_a = e1;
+            a.si_b = e2;
+            a.si_c = q1;
+            a.si_d = std::exp(-(e2 - e1) / 2.0) * std::pow(q1, e2 - e1);
+            a.si_e = 1.0 / (3.0 - e1);
+            break;
+        }
+        case SANS_SPINODAL: a.si_a = 1.0 / e1; a.si_b = e2; a.si_c = 1.0 + 0.5 * e2; break;
         default: break;
         }
         if (p->kind == SANS_TEUBNER_STREY) {

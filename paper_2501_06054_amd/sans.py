@@ -29,7 +29,9 @@ KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelep
         "micelle": 8, "hollow_cylinder": 9, "core_shell_cylinder": 10, "core_shell_ellipsoid": 11,
         "hollow_prism_thick": 12, "guinier": 13, "ornstein_zernike": 14, "dab": 15, "gauss_coil": 16,
         "poly_gauss_coil": 17, "teubner_strey": 18, "power_law": 19, "gaussian_peak": 20,
-        "lorentz_peak": 21, "mass_fractal": 22, "star_polymer": 23, "gauss_lorentz_gel": 24}
+        "lorentz_peak": 21, "mass_fractal": 22, "star_polymer": 23, "gauss_lorentz_gel": 24,
+        "fuzzy_sphere": 25, "vesicle": 26, "multilayer_vesicle": 27, "linear_pearls": 28,
+        "surface_fractal": 29, "two_power_law": 30, "guinier_porod": 31, "spinodal": 32}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 POLY_KIND = {"schulz": 0, "gaussian": 1}

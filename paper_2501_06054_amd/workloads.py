@@ -28,11 +28,13 @@ KINDS = ("sphere", "core_shell", "cylinder", "ellipsoid", "parallelepiped")
 #: revolution with spherical caps, hollow and core-shell bodies and the
 #: polymer micelle (Tables I-II)
 EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle", "hollow_cylinder",
-               "core_shell_cylinder", "core_shell_ellipsoid", "hollow_prism_thick")
+               "core_shell_cylinder", "core_shell_ellipsoid", "hollow_prism_thick", "fuzzy_sphere",
+               "vesicle", "multilayer_vesicle", "linear_pearls")
 #: shape-independent models: a cross-section in 1/cm, extra[0] = I(0)
 SHAPE_INDEPENDENT_KINDS = ("guinier", "ornstein_zernike", "dab", "gauss_coil", "poly_gauss_coil",
                            "teubner_strey", "power_law", "gaussian_peak", "lorentz_peak", "mass_fractal",
-                           "star_polymer", "gauss_lorentz_gel")
+                           "star_polymer", "gauss_lorentz_gel", "surface_fractal", "two_power_law",
+                           "guinier_porod", "spinodal")
 ORIENT_KINDS = ("fixed", "gaussian", "isotropic", "uniform_angles")
 MODES = ("mc", "quad", "surrogate")
 POLY_KINDS = ("schulz", "gaussian")
@@ -249,6 +251,16 @@ def mass_fractal() -> dict:
                               nx=256, ny=256))
 
 
+def multilayer_vesicle() -> dict:
+    """Multilamellar vesicles: 5 lipid shells of 10 A around an 80 A solvent
+    core, 20 A water layers between them, SLD shell/solvent 0.4e-6/6.3e-6,
+    volume fraction 0.05, 256x256, 1e9 neutrons."""
+    return dict(name="multilayer_vesicle", n=10**9, seed=20, exp_id=0,
+                params=params(kind="multilayer_vesicle", size=(80.0, 20.0, 0.0), shell=10.0,
+                              sld=(6.3e-6, 0.4e-6, 6.3e-6), extra=(5.0, 0.0, 0.0, 0.0), phi=0.05,
+                              nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -268,6 +280,7 @@ WORKLOADS = {
     "teubner_strey": teubner_strey,
     "poly_gauss_coil": poly_gauss_coil,
     "mass_fractal": mass_fractal,
+    "multilayer_vesicle": multilayer_vesicle,
 }
 
 

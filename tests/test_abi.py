@@ -127,6 +127,14 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
     (dict(kind="mass_fractal", size=(100.0, 0.0, 0.0), extra=(1.0, 1.0, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
     (dict(kind="star_polymer", size=(100.0, 0.0, 0.0), extra=(1.0, 0.5, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
     (dict(kind="gauss_lorentz_gel", size=(100.0, 0.0, 0.0), extra=(1.0, 1.0, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="vesicle", size=(50.0, 0.0, 0.0), shell=0.0), "SANS_E_INVALID_ARG"),
+    (dict(kind="linear_pearls", size=(20.0, 5.0, 0.0), extra=(2.5, 0.0, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="multilayer_vesicle", size=(50.0, 5.0, 0.0), shell=3.0, extra=(3.0, 0, 0, 0), poly=0.1),
+     "SANS_E_UNSUPPORTED"),
+    (dict(kind="surface_fractal", size=(50.0, 0.0, 0.0), extra=(1.0, 1.5, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="two_power_law", extra=(1.0, 1.0, 0.0, 3.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="guinier_porod", size=(50.0, 0.0, 0.0), extra=(1.0, 2.0, 1.5, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="spinodal", extra=(1.0, 0.0, 3.0, 0.0)), "SANS_E_INVALID_ARG"),
 ])
 def test_capped_body_params_rejected_without_gpu(S, over, code):
     from paper_2501_06054_amd import workloads as W
@@ -138,6 +146,6 @@ def test_capped_body_params_rejected_without_gpu(S, over, code):
 def test_unknown_kind_rejected_without_gpu(S):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=1.0))
-    sp.kind = 25
+    sp.kind = 33
     h = C.c_void_p()
     assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED

@@ -142,7 +142,7 @@ def test_batch_extra_models(S):
     hollow and core-shell bodies, polymer micelles and shape-independent
     models mixed with the other models: each equals its plain trace, and the
     extra models match the oracle."""
-    exps = _small_batch(n_exp=19, n_lo=2e5, n_hi=5e5)
+    exps = _small_batch(n_exp=21, n_lo=2e5, n_hi=5e5)
     caps = {1: dict(kind="barbell", size=(20.0, 300.0, 35.0), poly_mask=7, quad_n=40),
             4: dict(kind="capped_cylinder", size=(30.0, 120.0, 45.0), poly=0.1, poly_mask=7, quad_n=23),
             7: dict(kind="barbell", size=(15.0, 80.0, 15.0), poly_mask=7, quad_n=76),
@@ -162,6 +162,9 @@ def test_batch_extra_models(S):
             16: dict(kind="guinier", size=(45.0, 0.0, 0.0), extra=(3.0, 0.0, 0.0, 0.0), poly=0.0, sq_phi=0.0),
             17: dict(kind="power_law", extra=(1e-4, 3.2, 0.0, 0.0), poly=0.0, sq_phi=0.0),
             18: dict(kind="star_polymer", size=(70.0, 0.0, 0.0), extra=(3.0, 6.0, 0.0, 0.0), poly=0.0,
+                     sq_phi=0.0),
+            19: dict(kind="linear_pearls", size=(25.0, 12.0, 0.0), extra=(6.0, 0.0, 0.0, 0.0), poly_mask=1),
+            20: dict(kind="guinier_porod", size=(60.0, 0.0, 0.0), extra=(7.0, 1.0, 3.5, 0.0), poly=0.0,
                      sq_phi=0.0)}
     for e, over in caps.items():
         exps[e]["params"] = dict(exps[e]["params"], **over)
@@ -171,7 +174,7 @@ def test_batch_extra_models(S):
         ref = m.trace(x["n"], x["seed"], exp_id=e).cpu().numpy()
         m.close()
         assert np.allclose(got[e], ref, rtol=1e-9, atol=0), e
-    for e in (1, 4, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18):
+    for e in (1, 4, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20):
         x = exps[e]
         ref = oracle.trace(x["params"], x["n"], x["seed"], exp_id=e, nthreads=NTHREADS)
         assert np.array_equal(got[e] != 0, ref != 0), e

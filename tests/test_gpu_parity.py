@@ -228,6 +228,20 @@ PER_NEUTRON = {
     "mass_fractal_thin": (W.params(kind="mass_fractal", size=(40, 0, 0), extra=(2.0, 1.4, 0, 0)), 30011),
     "star_polymer": (W.params(kind="star_polymer", size=(70, 0, 0), extra=(3.0, 6.0, 0, 0)), 30011),
     "gauss_lorentz_gel": (W.params(kind="gauss_lorentz_gel", size=(25, 120, 0), extra=(2.0, 0.8, 0, 0)), 30011),
+    # sphere family
+    "fuzzy_sphere_poly": (W.params(kind="fuzzy_sphere", size=(60, 0, 0), shell=8.0, poly=0.15), 30011),
+    "vesicle_poly_py": (W.params(kind="vesicle", size=(80, 0, 0), shell=12.0, sld=(6.3e-6, 1e-6, 6.3e-6),
+                                 poly=0.2, sq_phi=0.1, sq_radius=95.0, phi=0.1), 30011),
+    "multilayer_vesicle": (W.workload("multilayer_vesicle")["params"], 50021),
+    "linear_pearls_poly": (W.params(kind="linear_pearls", size=(25, 12, 0), extra=(6.0, 0, 0, 0), poly=0.1),
+                           30011),
+    "quad_linear_pearls": (W.params(kind="linear_pearls", mode="quad", size=(25, 12, 0), extra=(6.0, 0, 0, 0),
+                                    poly=0.1), 2003),
+    # more shape-independent models
+    "surface_fractal": (W.params(kind="surface_fractal", size=(150, 0, 0), extra=(2.0, 2.4, 0, 0)), 30011),
+    "two_power_law": (W.params(kind="two_power_law", extra=(3e-5, 1.5, 0.02, 4.0)), 30011),
+    "guinier_porod": (W.params(kind="guinier_porod", size=(60, 0, 0), extra=(7.0, 1.0, 3.5, 0)), 30011),
+    "spinodal": (W.params(kind="spinodal", extra=(9.0, 0.02, 4.0, 0)), 30011),
 }
 
 
@@ -254,7 +268,7 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "poly_capped_cylinder_iso", "oriented_hollow_prism", "iso_poly_hollow_prism", "micelle_py",
              "oriented_core_shell_cylinder", "iso_poly_hollow_cylinder", "iso_core_shell_ellipsoid",
              "oriented_hollow_prism_thick", "teubner_strey", "poly_gauss_coil", "dab", "mass_fractal",
-             "star_polymer", "gaussian_peak"]
+             "star_polymer", "gaussian_peak", "multilayer_vesicle", "linear_pearls_poly", "spinodal"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -287,7 +301,7 @@ def test_quad_detector_parity(S, name):
 def test_pq_avg_matches_oracle(S):
     for name in ("quad_parallelepiped", "quad_spheroid", "quad_coreshell", "quad_capped_cylinder",
                  "quad_hollow_prism", "quad_micelle_poly", "quad_hollow_cylinder",
-                 "quad_core_shell_spheroid_poly", "quad_hollow_prism_thick"):
+                 "quad_core_shell_spheroid_poly", "quad_hollow_prism_thick", "quad_linear_pearls"):
         p, _ = PER_NEUTRON[name]
         m = S.Model(p)
         qs = np.concatenate([np.linspace(0.0, 0.06, 61), np.geomspace(1e-4, 0.3, 40)])
