@@ -59,7 +59,11 @@ typedef struct {
                               vesicle, 27 multilayer vesicle, 28 linear
                               pearls; shape-independent: 29 surface fractal,
                               30 two power law, 31 Guinier-Porod, 32
-                              spinodal                                      */
+                              spinodal, 33 Porod, 34 line, 35 two
+                              Lorentzians, 36 correlation length, 37 broad
+                              peak, 40 polymer with excluded volume;
+                              fractal aggregates of spheres: 38 homogeneous,
+                              39 core-shell                                 */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -576,7 +580,22 @@ static double micelle_f2(const double s[3], const double sld[3], const double ex
 
 /* Shape-independent models: the macroscopic cross-section dSigma/dOmega(q)
  * in 1/cm, scale = its value at q = 0 (extra[0]); the length is size[0]. */
-static int shape_independent(int kind) { return (kind >= 13 && kind <= 24) || (kind >= 29 && kind <= 32); }
+static int shape_independent(int kind)
+{
+    return (kind >= 13 && kind <= 24) || (kind >= 29 && kind <= 37) || kind == 40;
+}
+
+/* Fractal aggregates of spherical blocks (radius R0): Teixeira's structure
+ * factor of a mass fractal of dimension D with cut-off length xi, 1 plus the
+ * blocks' number density times the transform of the pair correlation
+ * (D / (4 pi R0^D)) r^(D - 3) exp(-r/xi). */
+static double teixeira_sq(double q, double r0, double xi, double d)
+{
+    if (q * xi < 1e-6) return 1.0 + tgamma(d + 1.0) * pow(xi / r0, d);
+    double qx = q * xi;
+    return 1.0 + d * tgamma(d - 1.0) * sin((d - 1.0) * atan(qx))
+                 / (pow(q * r0, d) * pow(1.0 + 1.0 / (qx * qx), 0.5 * (d - 1.0)));
+}
 
 static double shape_independent_iq(const orc_params* p, const double s[3], double q)
 {
@@ -667,6 +686,39 @@ static double shape_independent_iq(const orc_params* p, const double s[3], doubl
         double g = p->extra[2], xx = q / p->extra[1];
         return scale * (1.0 + 0.5 * g) * xx * xx / (0.5 * g + pow(xx, 2.0 + g));
     }
+    case 33: /* Porod: extra[0] q^-4 */
+        return scale * pow(q, -4.0);
+    case 34: /* line: extra[0] + extra[1] q */
+        return scale + p->extra[1] * q;
+    case 35: /* two generalised Lorentzians: extra[0] / (1 + (q xi1)^n1) +
+                extra[2] / (1 + (q xi2)^n2); xi1, xi2 = size[0], size[1];
+                n1 = extra[1], n2 = extra[3] */
+        return scale / (1.0 + pow(q * s[0], p->extra[1])) + p->extra[2] / (1.0 + pow(q * s[1], p->extra[3]));
+    case 36: /* correlation length: extra[0] q^-n + extra[2] / (1 + (q xi)^m);
+                n = extra[1], m = extra[3], xi = size[0] */
+        return scale * pow(q, -p->extra[1]) + p->extra[2] / (1.0 + pow(q * s[0], p->extra[3]));
+    case 37: /* broad peak: extra[0] q^-n + extra[2] / (1 + (|q - q0| xi)^m);
+                q0 = size[1], xi = size[0], n = extra[1], m = extra[3] */
+        return scale * pow(q, -p->extra[1]) + p->extra[2] / (1.0 + pow(fabs(q - s[1]) * s[0], p->extra[3]));
+    case 40: { /* polymer with excluded volume (Flory exponent nu = extra[1],
+                  radius of gyration size[0]): the chain's double average of
+                  exp(-U |t - u|^(2 nu)), U = (q Rg)^2 (2nu + 1)(2nu + 2)/6, through
+                  lower incomplete gamma functions; a series below U = 1e-3 */
+        double nu = p->extra[1];
+        double u = x * (2.0 * nu + 1.0) * (2.0 * nu + 2.0) / 6.0;
+        double s1 = 1.0 / (2.0 * nu), s2 = 1.0 / nu;
+        if (u < 1e-3) {
+            double a = 0.0, b = 0.0, t = 1.0;
+            for (int k = 0; k < 4; ++k) {
+                a += t / (s1 + k);
+                b += t / (s2 + k);
+                t *= -u / (k + 1.0);
+            }
+            return scale * (a - b) / nu;
+        }
+        double g1 = tgamma(s1) * orc_gamma_p(s1, u), g2 = tgamma(s2) * orc_gamma_p(s2, u);
+        return scale * (g1 / pow(u, s1) - g2 / pow(u, s2)) / nu;
+    }
     }
     return 0.0;
 }
@@ -721,6 +773,14 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
     if (shape_independent(p->kind)) return shape_independent_iq(p, s, q);
     if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
     if (p->kind >= 25 && p->kind <= 28) return sphere_family_f2(p, s, q);
+    if (p->kind == 38 || p->kind == 39) {
+        /* blocks: a sphere (38) or a core-shell sphere (39) of radius size[0]
+           (core), shell; fractal: xi = size[1], D = extra[1] */
+        double f = p->kind == 38 ? (p->sld[0] - p->sld[2]) * vol_sphere(s[0]) * orc_sph(q * s[0])
+                                 : amplitude(1, s, p->shell, p->sld, p->extra, q, 0.0, 0.0, 0.0, p->quad_n);
+        double r0 = p->kind == 38 ? s[0] : s[0] + p->shell;
+        return f * f * teixeira_sq(q, r0, s[1], p->extra[1]);
+    }
     double f = amplitude(p->kind, s, p->shell, p->sld, p->extra, q, qa, qb, qc, p->quad_n);
     return f * f;
 }
@@ -829,6 +889,14 @@ double orc_mean_volume(const orc_params* p)
             v += vol_sphere(ri + p->shell) - vol_sphere(ri);
         }
         return v;
+    }
+    case 38: /* fractal aggregate: the blocks' volume */
+        return vol_sphere(s[0]) * size_moment(p, b0 ? 3 : 0);
+    case 39: {
+        double r = s[0], t = p->shell;
+        if (!b0) return vol_sphere(r + t);
+        return 4.0 / 3.0 * ORC_PI * (r * r * r * size_moment(p, 3) + 3.0 * r * r * t * size_moment(p, 2)
+                                      + 3.0 * r * t * t * size_moment(p, 1) + t * t * t);
     }
     case 28: /* linear pearls: n spheres */
         return p->extra[0] * vol_sphere(s[0]) * size_moment(p, b0 ? 3 : 0);

@@ -1161,3 +1161,85 @@ def test_fractal_guinier_terms(orc, kind, dim):
     for x in (0.9e-6, 1.1e-6, 3e-5):
         q = x / xi
         assert 1.0 - orc.form_f2(p, q, (q, 0, 0)) == pytest.approx((a + 1) * (a + 2) * x * x / 6, rel=1e-4)
+
+
+# ------------------------------------------------------------------ the remaining shape-independent models
+
+def test_porod_is_the_spheres_large_q_average(orc):
+    # <F^2> of a sphere averaged over an oscillation at q R >> 1 tends to
+    # 2 pi drho^2 S / q^4 with S = 4 pi R^2 (Porod's law)
+    R, drho = 40.0, 1e-6
+    sph = W.params(kind="sphere", size=(R, 0, 0), sld=(drho, 0, 0))
+    por = W.params(kind="porod", extra=(2 * math.pi * drho ** 2 * 4 * math.pi * R ** 2, 0, 0, 0))
+    q0 = 400.0 / R
+    qs = q0 + np.linspace(-math.pi / R, math.pi / R, 2001)
+    avg = np.mean([orc.amplitude(sph, q, (q, 0, 0)) ** 2 * q ** 4 for q in qs])
+    assert avg / q0 ** 4 == pytest.approx(orc.form_f2(por, q0, (q0, 0, 0)), rel=2e-3)
+
+
+def test_line_is_linear(orc):
+    p = W.params(kind="line", extra=(0.7, 12.0, 0, 0))
+    f = lambda q: orc.form_f2(p, q, (q, 0, 0))
+    assert f(0.0) == pytest.approx(0.7, rel=1e-15)
+    assert f(0.01) + f(0.05) == pytest.approx(2 * f(0.03), rel=1e-14)
+
+
+@pytest.mark.parametrize("q", [0.001, 0.01, 0.04])
+def test_lorentzian_combinations_reduce(orc, q):
+    # exponents 2: two Ornstein-Zernike terms; power law plus Ornstein-Zernike;
+    # power law plus a Lorentzian peak of half width 1/xi
+    oz = lambda s, xi: orc.form_f2(W.params(kind="ornstein_zernike", size=(xi, 0, 0), extra=(s, 0, 0, 0)),
+                                   q, (q, 0, 0))
+    pl = orc.form_f2(W.params(kind="power_law", extra=(2e-4, 2.5, 0, 0)), q, (q, 0, 0))
+    two = W.params(kind="two_lorentzian", size=(80.0, 15.0, 0), extra=(3.0, 2.0, 0.5, 2.0))
+    assert orc.form_f2(two, q, (q, 0, 0)) == pytest.approx(oz(3.0, 80.0) + oz(0.5, 15.0), rel=1e-13)
+    cl = W.params(kind="correlation_length", size=(50.0, 0, 0), extra=(2e-4, 2.5, 1.5, 2.0))
+    assert orc.form_f2(cl, q, (q, 0, 0)) == pytest.approx(pl + oz(1.5, 50.0), rel=1e-13)
+    bp = W.params(kind="broad_peak", size=(120.0, 0.025, 0), extra=(2e-4, 2.5, 1.5, 2.0))
+    lp = orc.form_f2(W.params(kind="lorentz_peak", extra=(1.5, 0.025, 1 / 120.0, 0)), q, (q, 0, 0))
+    assert orc.form_f2(bp, q, (q, 0, 0)) == pytest.approx(pl + lp, rel=1e-13)
+    # a general exponent: half the Lorentzian term at q xi = 1
+    g = W.params(kind="two_lorentzian", size=(1.0 / q, 1.0, 0), extra=(3.0, 3.3, 0.0, 2.0))
+    assert orc.form_f2(g, q, (q, 0, 0)) == pytest.approx(1.5, rel=1e-13)
+
+
+@pytest.mark.parametrize("kind", ["fractal", "fractal_core_shell"])
+@pytest.mark.parametrize("q", [0.0, 1e-4, 0.005, 0.03])
+def test_fractal_aggregate(orc, kind, q):
+    """Blocks' F^2 times 1 + (D / R0^D) int r^(D-1) exp(-r/xi) sin(qr)/(qr) dr,
+    the transform of the blocks' pair correlation in a mass fractal."""
+    from scipy import integrate, special
+    R, t, xi, D = 20.0, 5.0, 300.0, 2.2
+    if kind == "fractal":
+        p = W.params(kind=kind, size=(R, xi, 0), sld=(1e-6, 0, 0), extra=(0, D, 0, 0))
+        block = W.params(kind="sphere", size=(R, 0, 0), sld=(1e-6, 0, 0))
+        r0 = R
+    else:
+        p = W.params(kind=kind, size=(R, xi, 0), shell=t, sld=(1e-6, 3e-6, 6.3e-6), extra=(0, D, 0, 0))
+        block = W.params(kind="core_shell", size=(R, 0, 0), shell=t, sld=(1e-6, 3e-6, 6.3e-6))
+        r0 = R + t
+    f = lambda r: math.exp(-r / xi) * (math.sin(q * r) / (q * r) if q * r > 0 else 1.0)
+    integral, _ = integrate.quad(f, 0.0, 80 * xi, weight="alg", wvar=(D - 1.0, 0.0), limit=2000,
+                                 epsabs=0.0, epsrel=1e-11)
+    sq = 1.0 + D / r0 ** D * integral
+    ref = orc.amplitude(block, q, (q, 0, 0)) ** 2 * sq
+    assert orc.form_f2(p, q, (q, 0, 0)) == pytest.approx(ref, rel=1e-8)
+    if q == 0.0:
+        assert sq == pytest.approx(1.0 + special.gamma(D + 1) * (xi / r0) ** D, rel=1e-9)
+
+
+@pytest.mark.parametrize("nu", [0.5, 0.588, 0.4])
+@pytest.mark.parametrize("q", [1e-5, 0.003, 0.02, 0.1])
+def test_excluded_volume_chain_average(orc, nu, q):
+    """2 int_0^1 (1 - x) exp(-U x^(2 nu)) dx, U = (q Rg)^2 (2nu + 1)(2nu + 2)/6;
+    nu = 1/2 is the Gaussian coil."""
+    from scipy import integrate
+    rg = 60.0
+    u = (q * rg) ** 2 * (2 * nu + 1) * (2 * nu + 2) / 6
+    ref, _ = integrate.quad(lambda x: 2 * (1 - x) * math.exp(-u * x ** (2 * nu)), 0, 1, epsabs=0,
+                            epsrel=1e-13, limit=200)
+    p = W.params(kind="polymer_excl_volume", size=(rg, 0, 0), extra=(2.0, nu, 0, 0))
+    assert orc.form_f2(p, q, (q, 0, 0)) == pytest.approx(2.0 * ref, rel=1e-10)
+    if nu == 0.5:
+        gc = W.params(kind="gauss_coil", size=(rg, 0, 0), extra=(2.0, 0, 0, 0))
+        assert orc.form_f2(p, q, (q, 0, 0)) == pytest.approx(orc.form_f2(gc, q, (q, 0, 0)), rel=1e-10)
