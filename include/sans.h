@@ -135,8 +135,21 @@ typedef enum {
                                     m1 = extra[1], qc = extra[2], m2 = extra[3] */
     SANS_GUINIER_POROD = 31,     /* Guinier (dimension s = extra[1], Rg = L)
                                     joined smoothly to Porod q^-m, m = extra[2] */
-    SANS_SPINODAL = 32           /* Furukawa: peak extra[0] at q_max = extra[1],
+    SANS_SPINODAL = 32,          /* Furukawa: peak extra[0] at q_max = extra[1],
                                     exponent gamma = extra[2]                  */
+    SANS_POROD = 33,             /* extra[0] q^-4                               */
+    SANS_LINE = 34,              /* extra[0] + extra[1] q (slope >= 0)           */
+    SANS_TWO_LORENTZIAN = 35,    /* extra[0]/(1 + (q size[0])^extra[1]) +
+                                    extra[2]/(1 + (q size[1])^extra[3])        */
+    SANS_CORRELATION_LENGTH = 36,/* extra[0] q^-extra[1] + extra[2]/(1 + (q L)^extra[3]) */
+    SANS_BROAD_PEAK = 37,        /* extra[0] q^-extra[1] + extra[2]/(1 + (|q - size[1]| L)^extra[3]) */
+    SANS_FRACTAL = 38,           /* particle: fractal aggregate of spheres of
+                                    radius size[0] (Teixeira; cut-off size[1],
+                                    dimension extra[1] in (1, 3])              */
+    SANS_FRACTAL_CORE_SHELL = 39,/* the same with core-shell blocks (shell,
+                                    sld = core, shell, solvent)                */
+    SANS_POLYMER_EXCL_VOLUME = 40 /* chain with excluded volume, Flory exponent
+                                    extra[1] in [1/3, 1], L its Rg              */
 } sans_kind;
 
 /* How the particle size and orientation enter the weight. */

@@ -114,7 +114,7 @@ struct TraceArgs {
     // further model constants: power law m; peaks q0, 1/width; mass fractal
     // D - 1, D (D + 1)/6; star f/(3f - 2), f - 1, 1/f; gel Lorentz scale and
     // length
-    double si_a, si_b, si_c, si_d, si_e;
+    double si_a, si_b, si_c, si_d, si_e, si_f, si_g;
     // sphere family: shells or pearls (n), the step between shells or the gap
     // between pearls (A)
     int32_t sf_n;
@@ -486,16 +486,21 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kPolyGaussCoil = 17, kTeubnerStrey = 18, kPowerLaw = 19, kGaussianPeak = 20,
               kLorentzPeak = 21, kMassFractal = 22, kStarPolymer = 23, kGaussLorentzGel = 24,
               kFuzzySphere = 25, kVesicle = 26, kMultilayerVesicle = 27, kLinearPearls = 28,
-              kSurfaceFractal = 29, kTwoPowerLaw = 30, kGuinierPorod = 31, kSpinodal = 32 };
+              kSurfaceFractal = 29, kTwoPowerLaw = 30, kGuinierPorod = 31, kSpinodal = 32, kPorod = 33,
+              kLine = 34, kTwoLorentzian = 35, kCorrelationLength = 36, kBroadPeak = 37, kFractal = 38,
+              kFractalCoreShell = 39, kPolymerExclVolume = 40 };
 
 // Shape-independent models: the weight is a cross-section in 1/cm of |Q|.
 template <int KIND>
 constexpr bool kShapeIndependent = (KIND >= kGuinier && KIND <= kGaussLorentzGel)
-                                   || (KIND >= kSurfaceFractal && KIND <= kSpinodal);
+                                   || (KIND >= kSurfaceFractal && KIND <= kBroadPeak)
+                                   || KIND == kPolymerExclVolume;
 
-// Isotropic sphere-based particles (fuzzy sphere, vesicles, pearl strings).
+// Isotropic sphere-based particles (fuzzy sphere, vesicles, pearl strings,
+// fractal aggregates of spheres).
 template <int KIND>
-constexpr bool kSphereFamily = KIND >= kFuzzySphere && KIND <= kLinearPearls;
+constexpr bool kSphereFamily = (KIND >= kFuzzySphere && KIND <= kLinearPearls) || KIND == kFractal
+                               || KIND == kFractalCoreShell;
 
 // Orientation enters the weight (the particles from the cylinder to the
 // thick hollow prism, but the micelle).
@@ -616,6 +621,38 @@ __device__ __forceinline__ float micelle_f2(const TraceArgs& a, double R, double
     return __builtin_fmaf(amp, amp, a.mic_n * a.mic_bc * a.mic_bc * __builtin_fmaf(-ps, ps, pc));
 }
 
+// Lower incomplete gamma g(s, x) = Gamma(s) P(s, x), FP64: its power series
+// below x = s + 1, else Gamma(s) less Legendre's continued fraction for the
+// upper one (modified Lentz); gs = Gamma(s).
+__device__ __forceinline__ double lower_gamma_d(double s, double x, double gs)
+{
+    const double pre = exp(s * log(x) - x);
+    if (x < s + 1.0) {
+        double term = 1.0 / s, sum = term;
+        for (int n = 1; n < 400; ++n) {
+            term *= x / (s + n);
+            sum += term;
+            if (fabs(term) < 1e-17 * sum) break;
+        }
+        return sum * pre;
+    }
+    const double tiny = 1e-300;
+    double b = x + 1.0 - s, c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int n = 1; n < 400; ++n) {
+        const double an = -n * (n - s);
+        b += 2.0;
+        d = __builtin_fma(an, d, b);
+        d = fabs(d) < tiny ? tiny : d;
+        c = b + an / c;
+        c = fabs(c) < tiny ? tiny : c;
+        d = 1.0 / d;
+        const double del = d * c;
+        h *= del;
+        if (fabs(del - 1.0) < 1e-16) break;
+    }
+    return gs - pre * h;
+}
+
 // Shape-independent models (Tables I-II): dSigma/dOmega(q) in 1/cm with the
 // length L = size[0]: Guinier exp(-(qL)^2/3), Ornstein-Zernike 1/(1 + (qL)^2),
 // Debye-Anderson-Brumberger 1/(1 + (qL)^2)^2, the Gaussian coil's Debye
@@ -687,11 +724,46 @@ __device__ __forceinline__ float shape_iq(const TraceArgs& a, double len, double
         // q^-s exp(-(q Rg)^2 / (3 - s)) up to q1, (D/G) q^-m beyond
         if (q <= a.si_c) return a.si_scale * (float)exp2(-a.si_a * log2(q)) * __expf(-x * (float)a.si_e);
         return a.si_scale * (float)(a.si_d * exp2(-a.si_b * log2(q)));
-    } else {
+    } else if constexpr (KIND == kSpinodal) {
         // spinodal: (1 + g/2) x^2 / (g/2 + x^(2 + g)), x = q / q_max (FP64 power)
         const double xs = q * a.si_a;
         const double v = a.si_c * xs * xs / (0.5 * a.si_b + exp2((2.0 + a.si_b) * log2(xs)));
         return a.si_scale * (float)v;
+    } else if constexpr (KIND == kPorod) {
+        const double iq2 = 1.0 / (q * q);
+        return a.si_scale * (float)(iq2 * iq2);
+    } else if constexpr (KIND == kLine) {
+        return (float)(__builtin_fma(a.si_a, q, (double)a.si_scale));
+    } else if constexpr (KIND == kTwoLorentzian) {
+        // two generalised Lorentzians (FP64 powers)
+        const double v = (double)a.si_scale / (1.0 + exp2(a.si_a * log2(q * a.si_d)))
+                       + a.si_b / (1.0 + exp2(a.si_c * log2(q * a.si_e)));
+        return (float)v;
+    } else if constexpr (KIND == kCorrelationLength || KIND == kBroadPeak) {
+        // a power law plus a generalised Lorentzian about 0 or about q0 (FP64)
+        const double dq = KIND == kBroadPeak ? fabs(q - a.si_e) : q;
+        const double v = (double)a.si_scale * exp2(-a.si_a * log2(q))
+                       + a.si_b / (1.0 + exp2(a.si_c * log2(dq * a.si_d)));
+        return (float)v;
+    } else {
+        // polymer with excluded volume: (g(s1, U)/U^s1 - g(s2, U)/U^s2)/nu with
+        // the lower incomplete gamma g, s1 = 1/(2 nu), s2 = 1/nu (FP64); a series
+        // below U = 1e-3
+        const double qr = q * len;
+        const double u = qr * qr * a.si_a, s1 = a.si_c, s2 = a.si_d;
+        double v;
+        if (u < 1e-3) {
+            double x1 = 0.0, x2 = 0.0, t = 1.0;
+            for (int k = 0; k < 4; ++k) {
+                x1 += t / (s1 + k);
+                x2 += t / (s2 + k);
+                t *= -u / (k + 1.0);
+            }
+            v = x1 - x2;
+        } else {
+            v = lower_gamma_d(s1, u, a.si_f) * exp(-s1 * log(u)) - lower_gamma_d(s2, u, a.si_g) * exp(-s2 * log(u));
+        }
+        return a.si_scale * (float)(v / a.si_b);
     }
 }
 
@@ -722,6 +794,31 @@ __device__ __forceinline__ float sphere_family_f2(const TraceArgs& a, double R, 
         }
         f *= a.cs_shell * k43pi;
         return f * f;
+    } else if constexpr (KIND == kFractal || KIND == kFractalCoreShell) {
+        // the blocks' F^2 times Teixeira's mass-fractal structure factor:
+        // 1 + D Gamma(D - 1) sin((D - 1) atan(q xi)) / ((q R0)^D (1 + 1/(q xi)^2)^((D - 1)/2)),
+        // its q -> 0 limit 1 + Gamma(D + 1) (xi/R0)^D below q xi = 1e-3 (FP64)
+        const float r = (float)R;
+        float f;
+        double r0 = R;
+        if constexpr (KIND == kFractal) {
+            f = a.contrast * k43pi * r * r * r * sph3j_d(q * R);
+        } else {
+            r0 = R + a.shell;
+            const float ro = (float)r0;
+            f = a.cs_core * k43pi * r * r * r * sph3j_d(q * R) + a.cs_shell * k43pi * ro * ro * ro * sph3j_d(q * r0);
+        }
+        // in FP64: the powers' arguments reach tens, where FP32 exponents
+        // would carry 1e-6 of relative error
+        const double qx = q * a.si_d, d = a.si_c;
+        double sq;
+        if (qx < 1e-3) {
+            sq = 1.0 + a.si_e * exp(d * log(a.si_d / r0));
+        } else {
+            const double num = a.si_a * sin((d - 1.0) * atan(qx));
+            sq = 1.0 + num * exp(-d * log(q * r0) - 0.5 * (d - 1.0) * log1p(1.0 / (qx * qx)));
+        }
+        return f * f * (float)sq;
     } else {
         const float r = (float)R;
         const float fs = a.contrast * k43pi * r * r * r * sph3j_d(q * R);

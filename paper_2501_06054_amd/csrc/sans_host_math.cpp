@@ -261,6 +261,10 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
         const int k[3] = {b0 ? 1 : 0, b1 ? 1 : 0, b2 ? 1 : 0};
         return c43 * expand_moment(f, k, poly_kind, poly);
     }
+    case 38:
+        return mean_volume(0, size, shell, poly, mask, poly_kind, extra);
+    case 39:
+        return mean_volume(1, size, shell, poly, mask, poly_kind, extra);
     case 25:
     case 28:
         // fuzzy sphere: the sphere; linear pearls: n spheres
@@ -284,7 +288,7 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
         return v;
     }
     case 13: case 14: case 15: case 16: case 17: case 18: case 19: case 20: case 21: case 22: case 23:
-    case 24: case 29: case 30: case 31: case 32:
+    case 24: case 29: case 30: case 31: case 32: case 33: case 34: case 35: case 36: case 37: case 40:
         return 1.0;  // shape-independent: no particles (the weight uses the cross-section)
     case 12: {
         // the box minus its cavity (monodisperse)

@@ -526,7 +526,15 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 29: batch_tile<29>(a, tl.first, tl.count, hist, tab); break;
         case 30: batch_tile<30>(a, tl.first, tl.count, hist, tab); break;
         case 31: batch_tile<31>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<32>(a, tl.first, tl.count, hist, tab); break;
+        case 32: batch_tile<32>(a, tl.first, tl.count, hist, tab); break;
+        case 33: batch_tile<33>(a, tl.first, tl.count, hist, tab); break;
+        case 34: batch_tile<34>(a, tl.first, tl.count, hist, tab); break;
+        case 35: batch_tile<35>(a, tl.first, tl.count, hist, tab); break;
+        case 36: batch_tile<36>(a, tl.first, tl.count, hist, tab); break;
+        case 37: batch_tile<37>(a, tl.first, tl.count, hist, tab); break;
+        case 38: batch_tile<38>(a, tl.first, tl.count, hist, tab); break;
+        case 39: batch_tile<39>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<40>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -792,6 +800,14 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(30)
         SANS_CASE(31)
         SANS_CASE(32)
+        SANS_CASE(33)
+        SANS_CASE(34)
+        SANS_CASE(35)
+        SANS_CASE(36)
+        SANS_CASE(37)
+        SANS_CASE(38)
+        SANS_CASE(39)
+        SANS_CASE(40)
     }
 #undef SANS_CASE
     return nullptr;
@@ -839,6 +855,14 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(30)
         SANS_CASE(31)
         SANS_CASE(32)
+        SANS_CASE(33)
+        SANS_CASE(34)
+        SANS_CASE(35)
+        SANS_CASE(36)
+        SANS_CASE(37)
+        SANS_CASE(38)
+        SANS_CASE(39)
+        SANS_CASE(40)
     }
 #undef SANS_CASE
     return nullptr;
@@ -883,6 +907,14 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(30)
         SANS_CASE(31)
         SANS_CASE(32)
+        SANS_CASE(33)
+        SANS_CASE(34)
+        SANS_CASE(35)
+        SANS_CASE(36)
+        SANS_CASE(37)
+        SANS_CASE(38)
+        SANS_CASE(39)
+        SANS_CASE(40)
     }
 #undef SANS_CASE
     return nullptr;
@@ -927,6 +959,14 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(30)
         SANS_CASE(31)
         SANS_CASE(32)
+        SANS_CASE(33)
+        SANS_CASE(34)
+        SANS_CASE(35)
+        SANS_CASE(36)
+        SANS_CASE(37)
+        SANS_CASE(38)
+        SANS_CASE(39)
+        SANS_CASE(40)
     }
 #undef SANS_CASE
     return nullptr;
@@ -968,6 +1008,14 @@ PqFn pick_pq(int kind)
     case 30: return k_pq_avg<30>;
     case 31: return k_pq_avg<31>;
     case 32: return k_pq_avg<32>;
+    case 33: return k_pq_avg<33>;
+    case 34: return k_pq_avg<34>;
+    case 35: return k_pq_avg<35>;
+    case 36: return k_pq_avg<36>;
+    case 37: return k_pq_avg<37>;
+    case 38: return k_pq_avg<38>;
+    case 39: return k_pq_avg<39>;
+    case 40: return k_pq_avg<40>;
     }
     return nullptr;
 }
@@ -1015,11 +1063,15 @@ bool finite(double x) { return std::isfinite(x); }
 bool is_shape_independent(int kind)
 {
     return (kind >= SANS_GUINIER && kind <= SANS_GAUSS_LORENTZ_GEL)
-           || (kind >= SANS_SURFACE_FRACTAL && kind <= SANS_SPINODAL);
+           || (kind >= SANS_SURFACE_FRACTAL && kind <= SANS_BROAD_PEAK) || kind == SANS_POLYMER_EXCL_VOLUME;
 }
 
 // Isotropic sphere-based particles.
-bool is_sphere_family(int kind) { return kind >= SANS_FUZZY_SPHERE && kind <= SANS_LINEAR_PEARLS; }
+bool is_sphere_family(int kind)
+{
+    return (kind >= SANS_FUZZY_SPHERE && kind <= SANS_LINEAR_PEARLS) || kind == SANS_FRACTAL
+           || kind == SANS_FRACTAL_CORE_SHELL;
+}
 
 // Orientation enters the weight (the particles from the cylinder to the thick
 // hollow prism, but the micelle).
@@ -1032,7 +1084,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 32) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 40) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -1050,11 +1102,15 @@ int validate(const sans_params* p)
     int nsize = p->kind <= 1 ? 1 : (two_sizes ? 2 : 3);
     if (is_shape_independent(p->kind))
         nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK
-                 || p->kind == SANS_TWO_POWER_LAW || p->kind == SANS_SPINODAL)
+                 || p->kind == SANS_TWO_POWER_LAW || p->kind == SANS_SPINODAL || p->kind == SANS_POROD
+                 || p->kind == SANS_LINE)
                     ? 0
-                : (p->kind == SANS_TEUBNER_STREY || p->kind == SANS_GAUSS_LORENTZ_GEL) ? 2
-                                                                                       : 1;
-    if (is_sphere_family(p->kind)) nsize = 1;
+                : (p->kind == SANS_TEUBNER_STREY || p->kind == SANS_GAUSS_LORENTZ_GEL
+                   || p->kind == SANS_TWO_LORENTZIAN)
+                    ? 2
+                    : 1;
+    if (is_sphere_family(p->kind))
+        nsize = (p->kind == SANS_FRACTAL || p->kind == SANS_FRACTAL_CORE_SHELL) ? 2 : 1;
     for (int k = 0; k < nsize; ++k)
         if (!(p->size[k] > 0.0) || !finite(p->size[k])) return fail(SANS_E_INVALID_ARG, "size must be > 0");
     if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
@@ -1106,6 +1162,19 @@ int validate(const sans_params* p)
         if (p->kind == SANS_GUINIER_POROD
             && !(p->extra[1] >= 0.0 && p->extra[1] < 3.0 && p->extra[2] > p->extra[1] && p->extra[2] <= 10.0))
             return fail(SANS_E_INVALID_ARG, "Guinier-Porod: need 0 <= s = extra[1] < 3 and s < m = extra[2] <= 10");
+        if (p->kind == SANS_LINE && !(p->extra[1] >= 0.0 && finite(p->extra[1])))
+            return fail(SANS_E_INVALID_ARG, "line: slope extra[1] must be >= 0");
+        if ((p->kind == SANS_TWO_LORENTZIAN || p->kind == SANS_CORRELATION_LENGTH || p->kind == SANS_BROAD_PEAK)
+            && !(p->extra[1] >= 0.0 && p->extra[1] <= 10.0 && p->extra[2] >= 0.0 && finite(p->extra[2])
+                 && p->extra[3] > 0.0 && p->extra[3] <= 10.0))
+            return fail(SANS_E_INVALID_ARG, "need exponents extra[1] in [0, 10] (> 0 for two Lorentzians), "
+                                            "extra[3] in (0, 10] and a scale extra[2] >= 0");
+        if ((p->kind == SANS_TWO_LORENTZIAN) && !(p->extra[1] > 0.0))
+            return fail(SANS_E_INVALID_ARG, "two Lorentzians: exponent extra[1] must be > 0");
+        if (p->kind == SANS_BROAD_PEAK && !(p->size[1] >= 0.0 && finite(p->size[1])))
+            return fail(SANS_E_INVALID_ARG, "broad peak: position size[1] must be >= 0");
+        if (p->kind == SANS_POLYMER_EXCL_VOLUME && !(p->extra[1] >= 1.0 / 3.0 && p->extra[1] <= 1.0))
+            return fail(SANS_E_INVALID_ARG, "excluded-volume polymer: Flory exponent extra[1] must be in [1/3, 1]");
         if (p->kind == SANS_SPINODAL
             && !(p->extra[1] > 0.0 && finite(p->extra[1]) && p->extra[2] > 0.0 && p->extra[2] <= 10.0))
             return fail(SANS_E_INVALID_ARG, "spinodal: need q_max = extra[1] > 0 and 0 < gamma = extra[2] <= 10");
@@ -1113,7 +1182,7 @@ int validate(const sans_params* p)
         if (p->sq_phi > 0.0) return fail(SANS_E_UNSUPPORTED, "shape-independent model: no structure factor");
     }
     if (is_sphere_family(p->kind)) {
-        if (p->kind == SANS_FUZZY_SPHERE && !(p->shell >= 0.0 && finite(p->shell)))
+        if ((p->kind == SANS_FUZZY_SPHERE || p->kind == SANS_FRACTAL_CORE_SHELL) && !(p->shell >= 0.0 && finite(p->shell)))
             return fail(SANS_E_INVALID_ARG, "fuzzy sphere: the fuzz width (shell) must be >= 0");
         if ((p->kind == SANS_VESICLE || p->kind == SANS_MULTILAYER_VESICLE) && !(p->shell > 0.0 && finite(p->shell)))
             return fail(SANS_E_INVALID_ARG, "vesicle: the shell thickness must be > 0");
@@ -1123,6 +1192,9 @@ int validate(const sans_params* p)
             return fail(SANS_E_INVALID_ARG, "need a gap size[1] >= 0 and an integer count extra[0] in 1..1000");
         if (p->kind == SANS_MULTILAYER_VESICLE && p->poly > 0.0 && p->poly_mask != 0)
             return fail(SANS_E_UNSUPPORTED, "multilayer vesicle: monodisperse only");
+        if ((p->kind == SANS_FRACTAL || p->kind == SANS_FRACTAL_CORE_SHELL)
+            && !(p->extra[1] > 1.0 && p->extra[1] <= 3.0))
+            return fail(SANS_E_INVALID_ARG, "fractal aggregate: dimension extra[1] must be in (1, 3]");
     }
     if (p->kind == SANS_POLYMER_MICELLE) {
         if (!(p->extra[0] >= 1.0 && finite(p->extra[0])))
@@ -1258,6 +1330,13 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     if (is_sphere_family(p->kind)) {
         a.sf_n = (int32_t)p->extra[0];
         a.sf_gap = p->size[1];
+        if (p->kind == SANS_FRACTAL || p->kind == SANS_FRACTAL_CORE_SHELL) {
+            const double d = p->extra[1];
+            a.si_a = d * std::tgamma(d - 1.0);
+            a.si_c = d;
+            a.si_d = p->size[1];
+            a.si_e = std::tgamma(d + 1.0);
+        }
     }
     if (p->kind == SANS_CORE_SHELL_CYLINDER) {
         a.cs_face = p->extra[0];
@@ -1295,6 +1374,30 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
             break;
         }
         case SANS_SPINODAL: a.si_a = 1.0 / e1; a.si_b = e2; a.si_c = 1.0 + 0.5 * e2; break;
+        case SANS_LINE: a.si_a = e1; break;
+        case SANS_TWO_LORENTZIAN:
+            a.si_a = e1;
+            a.si_b = e2;
+            a.si_c = p->extra[3];
+            a.si_d = p->size[0];
+            a.si_e = p->size[1];
+            break;
+        case SANS_CORRELATION_LENGTH:
+        case SANS_BROAD_PEAK:
+            a.si_a = e1;
+            a.si_b = e2;
+            a.si_c = p->extra[3];
+            a.si_d = p->size[0];
+            a.si_e = p->size[1];
+            break;
+        case SANS_POLYMER_EXCL_VOLUME:
+            a.si_a = (2.0 * e1 + 1.0) * (2.0 * e1 + 2.0) / 6.0;
+            a.si_b = e1;
+            a.si_c = 0.5 / e1;
+            a.si_d = 1.0 / e1;
+            a.si_f = std::tgamma(0.5 / e1);
+            a.si_g = std::tgamma(1.0 / e1);
+            break;
         default: break;
         }
         if (p->kind == SANS_TEUBNER_STREY) {

@@ -29,12 +29,13 @@ KINDS = ("sphere", "core_shell", "cylinder", "ellipsoid", "parallelepiped")
 #: polymer micelle (Tables I-II)
 EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle", "hollow_cylinder",
                "core_shell_cylinder", "core_shell_ellipsoid", "hollow_prism_thick", "fuzzy_sphere",
-               "vesicle", "multilayer_vesicle", "linear_pearls")
+               "vesicle", "multilayer_vesicle", "linear_pearls", "fractal", "fractal_core_shell")
 #: shape-independent models: a cross-section in 1/cm, extra[0] = I(0)
 SHAPE_INDEPENDENT_KINDS = ("guinier", "ornstein_zernike", "dab", "gauss_coil", "poly_gauss_coil",
                            "teubner_strey", "power_law", "gaussian_peak", "lorentz_peak", "mass_fractal",
                            "star_polymer", "gauss_lorentz_gel", "surface_fractal", "two_power_law",
-                           "guinier_porod", "spinodal")
+                           "guinier_porod", "spinodal", "porod", "line", "two_lorentzian", "correlation_length",
+                           "broad_peak", "polymer_excl_volume")
 ORIENT_KINDS = ("fixed", "gaussian", "isotropic", "uniform_angles")
 MODES = ("mc", "quad", "surrogate")
 POLY_KINDS = ("schulz", "gaussian")
@@ -261,6 +262,14 @@ def multilayer_vesicle() -> dict:
                               nx=256, ny=256))
 
 
+def polymer_excl_volume() -> dict:
+    """Swollen polymer chains (Flory exponent 0.588, Rg = 80 A), I(0) =
+    10 / cm, 256x256, 1e9 neutrons (incomplete gamma functions in FP64)."""
+    return dict(name="polymer_excl_volume", n=10**9, seed=21, exp_id=0,
+                params=params(kind="polymer_excl_volume", size=(80.0, 0.0, 0.0), extra=(10.0, 0.588, 0.0, 0.0),
+                              nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -281,6 +290,7 @@ WORKLOADS = {
     "poly_gauss_coil": poly_gauss_coil,
     "mass_fractal": mass_fractal,
     "multilayer_vesicle": multilayer_vesicle,
+    "polymer_excl_volume": polymer_excl_volume,
 }
 
 

@@ -142,7 +142,7 @@ def test_batch_extra_models(S):
     hollow and core-shell bodies, polymer micelles and shape-independent
     models mixed with the other models: each equals its plain trace, and the
     extra models match the oracle."""
-    exps = _small_batch(n_exp=21, n_lo=2e5, n_hi=5e5)
+    exps = _small_batch(n_exp=23, n_lo=2e5, n_hi=5e5)
     caps = {1: dict(kind="barbell", size=(20.0, 300.0, 35.0), poly_mask=7, quad_n=40),
             4: dict(kind="capped_cylinder", size=(30.0, 120.0, 45.0), poly=0.1, poly_mask=7, quad_n=23),
             7: dict(kind="barbell", size=(15.0, 80.0, 15.0), poly_mask=7, quad_n=76),
@@ -165,6 +165,10 @@ def test_batch_extra_models(S):
                      sq_phi=0.0),
             19: dict(kind="linear_pearls", size=(25.0, 12.0, 0.0), extra=(6.0, 0.0, 0.0, 0.0), poly_mask=1),
             20: dict(kind="guinier_porod", size=(60.0, 0.0, 0.0), extra=(7.0, 1.0, 3.5, 0.0), poly=0.0,
+                     sq_phi=0.0),
+            21: dict(kind="fractal_core_shell", size=(20.0, 250.0, 0.0), shell=5.0, sld=(1e-6, 3e-6, 6.3e-6),
+                     extra=(0.0, 2.5, 0.0, 0.0), poly_mask=1),
+            22: dict(kind="polymer_excl_volume", size=(80.0, 0.0, 0.0), extra=(10.0, 0.588, 0.0, 0.0), poly=0.0,
                      sq_phi=0.0)}
     for e, over in caps.items():
         exps[e]["params"] = dict(exps[e]["params"], **over)
@@ -174,7 +178,7 @@ def test_batch_extra_models(S):
         ref = m.trace(x["n"], x["seed"], exp_id=e).cpu().numpy()
         m.close()
         assert np.allclose(got[e], ref, rtol=1e-9, atol=0), e
-    for e in (1, 4, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20):
+    for e in (1, 4, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22):
         x = exps[e]
         ref = oracle.trace(x["params"], x["n"], x["seed"], exp_id=e, nthreads=NTHREADS)
         assert np.array_equal(got[e] != 0, ref != 0), e

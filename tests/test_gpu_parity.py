@@ -242,6 +242,19 @@ PER_NEUTRON = {
     "two_power_law": (W.params(kind="two_power_law", extra=(3e-5, 1.5, 0.02, 4.0)), 30011),
     "guinier_porod": (W.params(kind="guinier_porod", size=(60, 0, 0), extra=(7.0, 1.0, 3.5, 0)), 30011),
     "spinodal": (W.params(kind="spinodal", extra=(9.0, 0.02, 4.0, 0)), 30011),
+    "porod": (W.params(kind="porod", extra=(1e-7, 0, 0, 0)), 30011),
+    "line": (W.params(kind="line", extra=(0.5, 40.0, 0, 0)), 30011),
+    "two_lorentzian": (W.params(kind="two_lorentzian", size=(80.0, 15.0, 0), extra=(3.0, 2.6, 0.5, 1.7)), 30011),
+    "correlation_length": (W.params(kind="correlation_length", size=(50.0, 0, 0), extra=(2e-4, 2.5, 1.5, 2.2)),
+                           30011),
+    "broad_peak": (W.params(kind="broad_peak", size=(120.0, 0.025, 0), extra=(2e-4, 2.5, 1.5, 2.0)), 30011),
+    "fractal_poly": (W.params(kind="fractal", size=(20.0, 300.0, 0), sld=(1e-6, 0, 0), extra=(0, 2.2, 0, 0),
+                              poly=0.1, phi=0.05), 30011),
+    "fractal_core_shell": (W.params(kind="fractal_core_shell", size=(20.0, 250.0, 0), shell=5.0,
+                                    sld=(1e-6, 3e-6, 6.3e-6), extra=(0, 2.5, 0, 0), phi=0.05), 30011),
+    "polymer_excl_volume": (W.workload("polymer_excl_volume")["params"], 50021),
+    "polymer_excl_volume_compact": (W.params(kind="polymer_excl_volume", size=(150.0, 0, 0),
+                                             extra=(3.0, 0.34, 0, 0)), 30011),
 }
 
 
@@ -268,7 +281,8 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "poly_capped_cylinder_iso", "oriented_hollow_prism", "iso_poly_hollow_prism", "micelle_py",
              "oriented_core_shell_cylinder", "iso_poly_hollow_cylinder", "iso_core_shell_ellipsoid",
              "oriented_hollow_prism_thick", "teubner_strey", "poly_gauss_coil", "dab", "mass_fractal",
-             "star_polymer", "gaussian_peak", "multilayer_vesicle", "linear_pearls_poly", "spinodal"]
+             "star_polymer", "gaussian_peak", "multilayer_vesicle", "linear_pearls_poly", "spinodal",
+             "fractal_poly", "polymer_excl_volume", "broad_peak"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
