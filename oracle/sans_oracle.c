@@ -63,7 +63,9 @@ typedef struct {
                               Lorentzians, 36 correlation length, 37 broad
                               peak, 40 polymer with excluded volume;
                               fractal aggregates of spheres: 38 homogeneous,
-                              39 core-shell                                 */
+                              39 core-shell; oriented: 41 elliptical
+                              cylinder, 42 core-shell bicelle, 43 core-shell
+                              parallelepiped                                */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -540,6 +542,34 @@ static double amplitude(int kind, const double s[3], double shell, const double 
     case 12: /* hollow prism, walls of thickness shell: the box minus its cavity */
         return drho * (box_amp(s[0], s[1], s[2], qa, qb, qc)
                        - box_amp(s[0] - 2.0 * shell, s[1] - 2.0 * shell, s[2] - 2.0 * shell, qa, qb, qc));
+    case 41: { /* elliptical cylinder: semi-axes s0 along A, s1 along B, length s2
+                  along C; the ellipse's transform is the disc's at the scaled
+                  projection sqrt((s0 Q_A)^2 + (s1 Q_B)^2) */
+        double x = sqrt((s[0] * qa) * (s[0] * qa) + (s[1] * qb) * (s[1] * qb));
+        return drho * ORC_PI * s[0] * s[1] * s[2] * orc_sinc(0.5 * qc * s[2]) * orc_lambda1(x);
+    }
+    case 42: { /* core-shell bicelle: core (R, L), face layers of thickness extra[0]
+                  on the ends (SLD extra[1]), a rim of thickness shell around the
+                  whole (SLD sld[1]): core, core + faces, and the outer cylinder
+                  with their contrast steps */
+        double qab2 = q * q - qc * qc;
+        double qab = qab2 > 0.0 ? sqrt(qab2) : 0.0;
+        double tf = extra[0], rf = extra[1];
+        return (sld[0] - rf) * cyl_amp(s[0], s[1], qab, qc)
+             + (rf - sld[1]) * cyl_amp(s[0], s[1] + 2.0 * tf, qab, qc)
+             + (sld[1] - sld[2]) * cyl_amp(s[0] + shell, s[1] + 2.0 * tf, qab, qc);
+    }
+    case 43: { /* core-shell parallelepiped: the core box and, on each pair of
+                  faces, a slab of thickness extra[k] covering just that face
+                  (SLD sld[1]); the two slabs normal to an axis sit at +-(edge +
+                  t)/2, so their sum is 2 cos(Q (edge + t)/2) times one slab */
+        double core = box_amp(s[0], s[1], s[2], qa, qb, qc);
+        double ta = extra[0], tb = extra[1], tc = extra[2];
+        double sa = 2.0 * cos(0.5 * qa * (s[0] + ta)) * box_amp(ta, s[1], s[2], qa, qb, qc);
+        double sb = 2.0 * cos(0.5 * qb * (s[1] + tb)) * box_amp(s[0], tb, s[2], qa, qb, qc);
+        double sc = 2.0 * cos(0.5 * qc * (s[2] + tc)) * box_amp(s[0], s[1], tc, qa, qb, qc);
+        return (sld[0] - sld[2]) * core + (sld[1] - sld[2]) * (sa + sb + sc);
+    }
     }
     return 0.0;
 }
@@ -786,7 +816,7 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
 }
 
 /* Orientation matters (the particles from 2 to 12 but the micelle). */
-static int anisotropic(int kind) { return kind >= 2 && kind != 8 && kind <= 12; }
+static int anisotropic(int kind) { return (kind >= 2 && kind != 8 && kind <= 12) || (kind >= 41 && kind <= 43); }
 
 /* Sizes scaled by the relative size draw y according to the mask. */
 static void scaled_sizes(const orc_params* p, double y, double s[3])
@@ -917,6 +947,24 @@ double orc_mean_volume(const orc_params* p)
         int bb[3] = {b0, b1, b2};
         return 4.0 / 3.0 * ORC_PI * prod_moment(p, s, be, bb, 3);
     }
+    case 41: /* pi a b L */
+        return ORC_PI * s[0] * s[1] * s[2] * size_moment(p, b0 + b1 + b2);
+    case 42: { /* the outer cylinder pi (R y^b0 + t)^2 (L y^b1 + 2 t_f) */
+        double al[3] = {s[0], s[0], s[1]}, be[3] = {p->shell, p->shell, 2.0 * p->extra[0]};
+        int bb[3] = {b0, b0, b1};
+        return ORC_PI * prod_moment(p, al, be, bb, 3);
+    }
+    case 43: { /* core plus the six face slabs */
+        double z[3] = {0.0, 0.0, 0.0};
+        double a0[3] = {s[0], s[1], s[2]};
+        int bb[3] = {b0, b1, b2};
+        double v = prod_moment(p, a0, z, bb, 3);
+        double pa[2] = {s[1], s[2]}, pb[2] = {s[0], s[2]}, pc[2] = {s[0], s[1]};
+        int ba[2] = {b1, b2}, bbb[2] = {b0, b2}, bc[2] = {b0, b1};
+        v += 2.0 * p->extra[0] * prod_moment(p, pa, z, ba, 2) + 2.0 * p->extra[1] * prod_moment(p, pb, z, bbb, 2)
+           + 2.0 * p->extra[2] * prod_moment(p, pc, z, bc, 2);
+        return v;
+    }
     case 12: { /* box minus cavity (monodisperse) */
         double t2 = 2.0 * p->shell;
         return s[0] * s[1] * s[2] - (s[0] - t2) * (s[1] - t2) * (s[2] - t2);
@@ -1039,7 +1087,8 @@ static double pq_avg_nodes(const orc_params* p, double q, const double qvec[3],
     int aniso = anisotropic(p->kind);
     int iso = aniso && p->orient_kind == 2;
     /* a spheroid (a = b, scaled alike) needs only the angle to its C axis */
-    int one_axis = (p->kind == 2 || p->kind == 5 || p->kind == 6 || p->kind == 9 || p->kind == 10)
+    int one_axis = (p->kind == 2 || p->kind == 5 || p->kind == 6 || p->kind == 9 || p->kind == 10
+                    || p->kind == 42)
                 || ((p->kind == 3 || p->kind == 11) && p->size[0] == p->size[1]
                     && (p->poly_mask & 1) == (p->poly_mask >> 1 & 1));
     double A[3], B[3], C[3];

@@ -1243,3 +1243,96 @@ def test_excluded_volume_chain_average(orc, nu, q):
     if nu == 0.5:
         gc = W.params(kind="gauss_coil", size=(rg, 0, 0), extra=(2.0, 0, 0, 0))
         assert orc.form_f2(p, q, (q, 0, 0)) == pytest.approx(orc.form_f2(gc, q, (q, 0, 0)), rel=1e-10)
+
+
+# ------------------------------------------------------------------ oriented: elliptical cylinder, bicelle, core-shell box
+
+def _ellcyl_ft(a, b, L, qv, nz=64, nr=48, nphi=96):
+    """int cos(Q.x) dV over the elliptic cylinder x = a rho cos phi,
+    y = b rho sin phi, |z| <= L/2 (Jacobian a b rho), product Gauss rule."""
+    z, wz = _gauss(-0.5 * L, 0.5 * L, nz)
+    r, wr = _gauss(0.0, 1.0, nr)
+    ph, wp = _gauss(0.0, 2 * math.pi, nphi)
+    x = a * r[:, None] * np.cos(ph)[None, :]
+    y = b * r[:, None] * np.sin(ph)[None, :]
+    arg = qv[0] * x[None] + qv[1] * y[None] + qv[2] * z[:, None, None]
+    return float(np.einsum("i,j,k,ijk->", wz, wr * r * a * b, wp, np.cos(arg)))
+
+
+@pytest.mark.parametrize("qv", [(0.0, 0.0, 0.0), (0.04, 0.0, 0.0), (0.0, 0.05, 0.0), (0.0, 0.0, 0.03),
+                                (0.03, -0.02, 0.015)])
+def test_elliptical_cylinder_is_its_transform(orc, qv):
+    a, b, L = 15.0, 40.0, 120.0
+    p = W.params(kind="elliptical_cylinder", size=(a, b, L), sld=(1.0, 0, 0))
+    q = math.sqrt(sum(x * x for x in qv))
+    got = orc.amplitude(p, q, qv, 1.0, (0.0, 0.0, 0.0))
+    assert got == pytest.approx(_ellcyl_ft(a, b, L, qv), rel=1e-9, abs=1e-10 * math.pi * a * b * L)
+    # a circular section is the cylinder
+    c = W.params(kind="elliptical_cylinder", size=(a, a, L), sld=(1.0, 0, 0))
+    cy = W.params(kind="cylinder", size=(a, L, 0), sld=(1.0, 0, 0))
+    assert orc.amplitude(c, q, qv, 1.0, (0.3, 0.9, 0.0)) == pytest.approx(
+        orc.amplitude(cy, q, qv, 1.0, (0.3, 0.9, 0.0)), rel=1e-12, abs=1e-12 * math.pi * a * a * L)
+
+
+@pytest.mark.parametrize("qab,qc", [(0.0, 0.0), (0.03, 0.01), (0.0, 0.05), (0.08, 0.0)])
+def test_core_shell_bicelle_is_its_layers(orc, qab, qc):
+    """Core (rho_c), the two face discs of radius R (rho_f), the rim around the
+    core and faces (rho_r), each region's transform by quadrature."""
+    R, L, tr, tf = 25.0, 60.0, 6.0, 8.0
+    rc, rr, rs, rf = 1.0e-6, 4.0e-6, 6.3e-6, 2.5e-6
+    p = W.params(kind="core_shell_bicelle", size=(R, L, 0), shell=tr, sld=(rc, rr, rs), extra=(tf, rf, 0, 0))
+    got = orc.amplitude(p, math.hypot(qab, qc), (qab, 0.0, qc), 1.0, (0.0, 0.0, 0.0))
+    core = _cyl_shell_ft(qab, qc, -0.5 * L, 0.5 * L, 0.0, R)
+    faces = (_cyl_shell_ft(qab, qc, 0.5 * L, 0.5 * L + tf, 0.0, R)
+             + _cyl_shell_ft(qab, qc, -0.5 * L - tf, -0.5 * L, 0.0, R))
+    rim = _cyl_shell_ft(qab, qc, -0.5 * L - tf, 0.5 * L + tf, R, R + tr)
+    ref = (rc - rs) * core + (rf - rs) * faces + (rr - rs) * rim
+    assert got == pytest.approx(ref, rel=1e-9, abs=1e-12 * math.pi * R * R * L * 1e-6)
+    # face SLD = rim SLD: the core-shell cylinder
+    p2 = dict(p, extra=(tf, rr, 0, 0))
+    cs = W.params(kind="core_shell_cylinder", size=(R, L, 0), shell=tr, sld=(rc, rr, rs), extra=(tf, 0, 0, 0))
+    q = math.hypot(qab, qc)
+    assert orc.amplitude(p2, q, (qab, 0, qc), 1.0, (0, 0, 0)) == pytest.approx(
+        orc.amplitude(cs, q, (qab, 0, qc), 1.0, (0, 0, 0)), rel=1e-12, abs=1e-20)
+
+
+@pytest.mark.parametrize("qv", [(0.0, 0.0, 0.0), (0.03, 0.0, 0.0), (0.02, -0.05, 0.01), (0.09, 0.04, 0.06)])
+def test_core_shell_parallelepiped_is_core_and_face_slabs(orc, qv):
+    A, B, Cc = 30.0, 50.0, 90.0
+    ta, tb, tc = 4.0, 6.0, 3.0
+    rc, rsh, rs = 1e-6, 3e-6, 6.3e-6
+    p = W.params(kind="core_shell_parallelepiped", size=(A, B, Cc), sld=(rc, rsh, rs), extra=(ta, tb, tc, 0))
+    q = math.sqrt(sum(x * x for x in qv))
+    got = orc.amplitude(p, q, qv, 1.0, (0.0, 0.0, 0.0))
+    core = _box_region_ft(qv, (-A / 2, -B / 2, -Cc / 2), (A / 2, B / 2, Cc / 2))
+    slabs = 0.0
+    for sgn in (-1.0, 1.0):
+        slabs += _box_region_ft(qv, (min(sgn * A / 2, sgn * (A / 2 + ta)), -B / 2, -Cc / 2),
+                                (max(sgn * A / 2, sgn * (A / 2 + ta)), B / 2, Cc / 2))
+        slabs += _box_region_ft(qv, (-A / 2, min(sgn * B / 2, sgn * (B / 2 + tb)), -Cc / 2),
+                                (A / 2, max(sgn * B / 2, sgn * (B / 2 + tb)), Cc / 2))
+        slabs += _box_region_ft(qv, (-A / 2, -B / 2, min(sgn * Cc / 2, sgn * (Cc / 2 + tc))),
+                                (A / 2, B / 2, max(sgn * Cc / 2, sgn * (Cc / 2 + tc))))
+    ref = (rc - rs) * core + (rsh - rs) * slabs
+    assert got == pytest.approx(ref, rel=1e-9, abs=1e-12 * A * B * Cc * 1e-6)
+    vol = A * B * Cc + 2 * (ta * B * Cc + tb * A * Cc + tc * A * B)
+    assert orc.mean_volume(p) == pytest.approx(vol, rel=1e-14)
+
+
+@pytest.mark.parametrize("kind,size,shell,extra,mask", [
+    ("elliptical_cylinder", (15.0, 40.0, 120.0), 0.0, (0.0,) * 4, 7),
+    ("core_shell_bicelle", (25.0, 60.0, 0.0), 6.0, (8.0, 2.5e-6, 0.0, 0.0), 3),
+    ("core_shell_parallelepiped", (30.0, 50.0, 90.0), 0.0, (4.0, 6.0, 3.0, 0.0), 5),
+])
+def test_oriented_mean_volume_by_quadrature(orc, kind, size, shell, extra, mask):
+    from scipy import integrate, stats
+    poly = 0.2
+    sld = (1.0, 1.0, 0.0) if kind != "core_shell_bicelle" else (1.0, 1.0, 0.0)
+    ex = extra if kind != "core_shell_bicelle" else (extra[0], 1.0, 0.0, 0.0)
+    p = W.params(kind=kind, size=size, shell=shell, extra=ex, poly=poly, poly_mask=mask, sld=sld)
+    mono = dict(p, poly=0.0)
+    a = 1.0 / poly ** 2
+    pdf = stats.gamma(a, scale=1.0 / a).pdf
+    vol = lambda y: orc.amplitude(mono, 0.0, (0.0, 0.0, 0.0), y, (0.0, 0.0, 0.0)) * pdf(y)
+    ref, _ = integrate.quad(vol, 0.0, 4.0, limit=200, epsabs=0.0, epsrel=1e-12)
+    assert orc.mean_volume(p) == pytest.approx(ref, rel=1e-9)
