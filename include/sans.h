@@ -148,8 +148,18 @@ typedef enum {
                                     dimension extra[1] in (1, 3])              */
     SANS_FRACTAL_CORE_SHELL = 39,/* the same with core-shell blocks (shell,
                                     sld = core, shell, solvent)                */
-    SANS_POLYMER_EXCL_VOLUME = 40 /* chain with excluded volume, Flory exponent
+    SANS_POLYMER_EXCL_VOLUME = 40, /* chain with excluded volume, Flory exponent
                                     extra[1] in [1/3, 1], L its Rg              */
+    /* Oriented particles (as SANS_CYLINDER .. SANS_HOLLOW_PRISM_THICK). */
+    SANS_ELLIPTICAL_CYLINDER = 41, /* semi-axes size[0] along A, size[1] along B,
+                                    length size[2] along C                     */
+    SANS_CORE_SHELL_BICELLE = 42,/* core radius size[0], length size[1]; face
+                                    layers of thickness extra[0] (SLD extra[1])
+                                    on the ends; a rim of thickness shell (SLD
+                                    sld[1]) around core and faces; axis C       */
+    SANS_CORE_SHELL_PARALLELEPIPED = 43 /* core edges size[0..2]; on each pair of
+                                    faces a slab of thickness extra[0..2] that
+                                    covers just that face, SLD sld[1]          */
 } sans_kind;
 
 /* How the particle size and orientation enter the weight. */

@@ -119,9 +119,14 @@ struct TraceArgs {
     // between pearls (A)
     int32_t sf_n;
     double sf_gap;
-    // core-shell cylinder: thickness of the shell on each end face (A)
+    // core-shell cylinder and bicelle: thickness of the shell on each end face
+    // (A); bicelle: contrasts core - face, face - rim, rim - solvent;
+    // core-shell parallelepiped: the face slabs' thicknesses (A)
     double cs_face;
     float fcs_face;
+    float bi_c[3];
+    double csp_t[3];
+    float fcsp_t[3];
     // run
     uint64_t first, n;
     uint32_t seed_lo, seed_hi, exp_id;
@@ -488,7 +493,8 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kFuzzySphere = 25, kVesicle = 26, kMultilayerVesicle = 27, kLinearPearls = 28,
               kSurfaceFractal = 29, kTwoPowerLaw = 30, kGuinierPorod = 31, kSpinodal = 32, kPorod = 33,
               kLine = 34, kTwoLorentzian = 35, kCorrelationLength = 36, kBroadPeak = 37, kFractal = 38,
-              kFractalCoreShell = 39, kPolymerExclVolume = 40 };
+              kFractalCoreShell = 39, kPolymerExclVolume = 40, kEllipticalCylinder = 41,
+              kCoreShellBicelle = 42, kCoreShellParallelepiped = 43 };
 
 // Shape-independent models: the weight is a cross-section in 1/cm of |Q|.
 template <int KIND>
@@ -505,14 +511,15 @@ constexpr bool kSphereFamily = (KIND >= kFuzzySphere && KIND <= kLinearPearls) |
 // Orientation enters the weight (the particles from the cylinder to the
 // thick hollow prism, but the micelle).
 template <int KIND>
-constexpr bool kAniso = KIND >= kCylinder && KIND <= kHollowPrismThick && KIND != kMicelle;
+constexpr bool kAniso = (KIND >= kCylinder && KIND <= kHollowPrismThick && KIND != kMicelle)
+                        || (KIND >= kEllipticalCylinder && KIND <= kCoreShellParallelepiped);
 
 // Bodies of revolution about C: cylinders (plain, hollow, core-shell),
 // barbell, capped cylinder (only the axis projection Q.C and Q_AB enter, the
 // third angle does not).
 template <int KIND>
 constexpr bool kOneAxis = KIND == kCylinder || KIND == kBarbell || KIND == kCappedCylinder
-                          || KIND == kHollowCylinder || KIND == kCoreShellCylinder;
+                          || KIND == kHollowCylinder || KIND == kCoreShellCylinder || KIND == kCoreShellBicelle;
 
 // The caps' part of the barbell / capped-cylinder amplitude (Tables I-II,
 // group A), in FP32: sum_i w_i cos(P + B t_i) 2J1(X s_i)/(X s_i) over the
@@ -904,6 +911,36 @@ __device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, doub
         const float cav = (float)ia * (float)ib * (float)ic * sinc_d(0.5 * qa * ia) * sinc_d(0.5 * qb * ib)
                         * sinc_d(0.5 * qc * ic);
         return a.contrast * (box - cav);
+    } else if constexpr (KIND == kEllipticalCylinder) {
+        // the ellipse's transform is the disc's at sqrt((a Q_A)^2 + (b Q_B)^2)
+        const double xa = qa * s[0], xb = qb * s[1];
+        const float x = (float)sqrt(xa * xa + xb * xb);
+        return a.contrast * (float)kPi * (float)s[0] * (float)s[1] * (float)s[2] * sinc_d(0.5 * qc * s[2])
+             * lambda1_f(x);
+    } else if constexpr (KIND == kCoreShellBicelle) {
+        // core (R, L), core + faces (R, L + 2 t_f), outer (R + rim, L + 2 t_f)
+        const double qab = sqrt(fmax(__builtin_fma(q, q, -qc * qc), 0.0));
+        const double lf = __builtin_fma(2.0, a.cs_face, s[1]), ro = s[0] + a.shell;
+        const float r = (float)s[0], len = (float)s[1], flf = (float)lf, fro = (float)ro;
+        const float disc = lambda1_f((float)(qab * s[0]));
+        const float core = r * r * len * sinc_d(0.5 * qc * s[1]) * disc;
+        const float ends = sinc_d(0.5 * qc * lf);
+        const float faces = r * r * flf * ends * disc;
+        const float outer = fro * fro * flf * ends * lambda1_f((float)(qab * ro));
+        return (float)kPi * (a.bi_c[0] * core + a.bi_c[1] * faces + a.bi_c[2] * outer);
+    } else if constexpr (KIND == kCoreShellParallelepiped) {
+        // the core box and the face slabs, each pair 2 cos(Q (edge + t)/2) times one slab
+        const float A = (float)s[0], B = (float)s[1], C = (float)s[2];
+        const float sa = sinc_d(0.5 * qa * s[0]), sb = sinc_d(0.5 * qb * s[1]), sc = sinc_d(0.5 * qc * s[2]);
+        float sn, ca, cb, cc;
+        sincos_phase(0.5 * qa * (s[0] + a.csp_t[0]), sn, ca);
+        sincos_phase(0.5 * qb * (s[1] + a.csp_t[1]), sn, cb);
+        sincos_phase(0.5 * qc * (s[2] + a.csp_t[2]), sn, cc);
+        const float ta = a.fcsp_t[0], tb = a.fcsp_t[1], tc = a.fcsp_t[2];
+        const float slabs = 2.0f * (ca * ta * B * C * sinc_d(0.5 * qa * a.csp_t[0]) * sb * sc
+                                    + cb * A * tb * C * sa * sinc_d(0.5 * qb * a.csp_t[1]) * sc
+                                    + cc * A * B * tc * sa * sb * sinc_d(0.5 * qc * a.csp_t[2]));
+        return a.contrast * A * B * C * sa * sb * sc + a.cs_shell * slabs;
     } else {
         return a.contrast * (float)s[0] * (float)s[1] * (float)s[2] * sinc_d(0.5 * qa * s[0])
              * sinc_d(0.5 * qb * s[1]) * sinc_d(0.5 * qc * s[2]);
@@ -971,6 +1008,30 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
                         * sinc_f(0.5f * qc * s[2]);
         const float cav = ia * ib * ic * sinc_f(0.5f * qa * ia) * sinc_f(0.5f * qb * ib) * sinc_f(0.5f * qc * ic);
         return a.contrast * (box - cav);
+    } else if constexpr (KIND == kEllipticalCylinder) {
+        const float xa = qa * s[0], xb = qb * s[1];
+        return a.contrast * (float)kPi * s[0] * s[1] * s[2] * sinc_f(0.5f * qc * s[2])
+             * lambda1_f(sqrtf(__builtin_fmaf(xa, xa, xb * xb)));
+    } else if constexpr (KIND == kCoreShellBicelle) {
+        const float qab = sqrtf(fmaxf(__builtin_fmaf(q, q, -qc * qc), 0.0f));
+        const float r = s[0], len = s[1], lf = __builtin_fmaf(2.0f, a.fcs_face, s[1]), ro = s[0] + a.fshell;
+        const float disc = lambda1_f(qab * r), ends = sinc_f(0.5f * qc * lf);
+        const float core = r * r * len * sinc_f(0.5f * qc * len) * disc;
+        const float faces = r * r * lf * ends * disc;
+        const float outer = ro * ro * lf * ends * lambda1_f(qab * ro);
+        return (float)kPi * (a.bi_c[0] * core + a.bi_c[1] * faces + a.bi_c[2] * outer);
+    } else if constexpr (KIND == kCoreShellParallelepiped) {
+        const float A = s[0], B = s[1], C = s[2];
+        const float ta = a.fcsp_t[0], tb = a.fcsp_t[1], tc = a.fcsp_t[2];
+        const float sa = sinc_f(0.5f * qa * A), sb = sinc_f(0.5f * qb * B), sc = sinc_f(0.5f * qc * C);
+        float sn, ca, cb, cc;
+        sincos_f(0.5f * qa * (A + ta), sn, ca);
+        sincos_f(0.5f * qb * (B + tb), sn, cb);
+        sincos_f(0.5f * qc * (C + tc), sn, cc);
+        const float slabs = 2.0f * (ca * ta * B * C * sinc_f(0.5f * qa * ta) * sb * sc
+                                    + cb * A * tb * C * sa * sinc_f(0.5f * qb * tb) * sc
+                                    + cc * A * B * tc * sa * sb * sinc_f(0.5f * qc * tc));
+        return a.contrast * A * B * C * sa * sb * sc + a.cs_shell * slabs;
     } else {
         return a.contrast * s[0] * s[1] * s[2] * sinc_f(0.5f * qa * s[0]) * sinc_f(0.5f * qb * s[1])
              * sinc_f(0.5f * qc * s[2]);

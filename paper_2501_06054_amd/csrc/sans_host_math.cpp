@@ -261,6 +261,23 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
         const int k[3] = {b0 ? 1 : 0, b1 ? 1 : 0, b2 ? 1 : 0};
         return c43 * expand_moment(f, k, poly_kind, poly);
     }
+    case 41:
+        return kPiH * size[0] * size[1] * size[2]
+             * size_moment(poly_kind, poly, (b0 ? 1 : 0) + (b1 ? 1 : 0) + (b2 ? 1 : 0));
+    case 42: {
+        // the outer cylinder pi (R y^b0 + rim)^2 (L y^b1 + 2 t_face)
+        const double f[3][2] = {{size[0], shell}, {size[0], shell}, {size[1], 2.0 * extra[0]}};
+        const int k[3] = {b0 ? 1 : 0, b0 ? 1 : 0, b1 ? 1 : 0};
+        return kPiH * expand_moment(f, k, poly_kind, poly);
+    }
+    case 43: {
+        // the core box and the six face slabs
+        const int k0 = b0 ? 1 : 0, k1 = b1 ? 1 : 0, k2 = b2 ? 1 : 0;
+        return size[0] * size[1] * size[2] * size_moment(poly_kind, poly, k0 + k1 + k2)
+             + 2.0 * (extra[0] * size[1] * size[2] * size_moment(poly_kind, poly, k1 + k2)
+                      + extra[1] * size[0] * size[2] * size_moment(poly_kind, poly, k0 + k2)
+                      + extra[2] * size[0] * size[1] * size_moment(poly_kind, poly, k0 + k1));
+    }
     case 38:
         return mean_volume(0, size, shell, poly, mask, poly_kind, extra);
     case 39:

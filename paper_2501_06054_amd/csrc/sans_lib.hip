@@ -534,7 +534,10 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 37: batch_tile<37>(a, tl.first, tl.count, hist, tab); break;
         case 38: batch_tile<38>(a, tl.first, tl.count, hist, tab); break;
         case 39: batch_tile<39>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<40>(a, tl.first, tl.count, hist, tab); break;
+        case 40: batch_tile<40>(a, tl.first, tl.count, hist, tab); break;
+        case 41: batch_tile<41>(a, tl.first, tl.count, hist, tab); break;
+        case 42: batch_tile<42>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<43>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -808,6 +811,9 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(38)
         SANS_CASE(39)
         SANS_CASE(40)
+        SANS_CASE(41)
+        SANS_CASE(42)
+        SANS_CASE(43)
     }
 #undef SANS_CASE
     return nullptr;
@@ -863,6 +869,9 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(38)
         SANS_CASE(39)
         SANS_CASE(40)
+        SANS_CASE(41)
+        SANS_CASE(42)
+        SANS_CASE(43)
     }
 #undef SANS_CASE
     return nullptr;
@@ -915,6 +924,9 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(38)
         SANS_CASE(39)
         SANS_CASE(40)
+        SANS_CASE(41)
+        SANS_CASE(42)
+        SANS_CASE(43)
     }
 #undef SANS_CASE
     return nullptr;
@@ -967,6 +979,9 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(38)
         SANS_CASE(39)
         SANS_CASE(40)
+        SANS_CASE(41)
+        SANS_CASE(42)
+        SANS_CASE(43)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1016,6 +1031,9 @@ PqFn pick_pq(int kind)
     case 38: return k_pq_avg<38>;
     case 39: return k_pq_avg<39>;
     case 40: return k_pq_avg<40>;
+    case 41: return k_pq_avg<41>;
+    case 42: return k_pq_avg<42>;
+    case 43: return k_pq_avg<43>;
     }
     return nullptr;
 }
@@ -1077,14 +1095,15 @@ bool is_sphere_family(int kind)
 // hollow prism, but the micelle).
 bool is_aniso(int kind)
 {
-    return kind >= SANS_CYLINDER && kind <= SANS_HOLLOW_PRISM_THICK && kind != SANS_POLYMER_MICELLE;
+    return (kind >= SANS_CYLINDER && kind <= SANS_HOLLOW_PRISM_THICK && kind != SANS_POLYMER_MICELLE)
+           || (kind >= SANS_ELLIPTICAL_CYLINDER && kind <= SANS_CORE_SHELL_PARALLELEPIPED);
 }
 
 int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 40) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 43) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -1098,7 +1117,8 @@ int validate(const sans_params* p)
     if (p->orient_kind < 0 || p->orient_kind > 3) return fail(SANS_E_UNSUPPORTED, "unknown orientation kind");
     if (p->tally < 0 || p->tally > 4) return fail(SANS_E_UNSUPPORTED, "unknown tally strategy");
     const bool two_sizes = p->kind == SANS_CYLINDER || p->kind == SANS_POLYMER_MICELLE
-                           || p->kind == SANS_HOLLOW_CYLINDER || p->kind == SANS_CORE_SHELL_CYLINDER;
+                           || p->kind == SANS_HOLLOW_CYLINDER || p->kind == SANS_CORE_SHELL_CYLINDER
+                           || p->kind == SANS_CORE_SHELL_BICELLE;
     int nsize = p->kind <= 1 ? 1 : (two_sizes ? 2 : 3);
     if (is_shape_independent(p->kind))
         nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK
@@ -1124,9 +1144,17 @@ int validate(const sans_params* p)
         return fail(SANS_E_INVALID_ARG, "shell must be >= 0");
     if (p->kind == SANS_HOLLOW_PRISM && !(p->shell > 0.0 && finite(p->shell)))
         return fail(SANS_E_INVALID_ARG, "hollow prism: wall thickness (shell) must be > 0");
-    if ((p->kind == SANS_CORE_SHELL_CYLINDER || p->kind == SANS_CORE_SHELL_ELLIPSOID)
+    if ((p->kind == SANS_CORE_SHELL_CYLINDER || p->kind == SANS_CORE_SHELL_ELLIPSOID
+         || p->kind == SANS_CORE_SHELL_BICELLE)
         && !(p->shell >= 0.0 && finite(p->shell)))
         return fail(SANS_E_INVALID_ARG, "shell must be >= 0");
+    if (p->kind == SANS_CORE_SHELL_BICELLE
+        && !(p->extra[0] >= 0.0 && finite(p->extra[0]) && finite(p->extra[1])))
+        return fail(SANS_E_INVALID_ARG, "bicelle: face thickness extra[0] >= 0 and a finite face SLD extra[1]");
+    if (p->kind == SANS_CORE_SHELL_PARALLELEPIPED
+        && !(p->extra[0] >= 0.0 && p->extra[1] >= 0.0 && p->extra[2] >= 0.0 && finite(p->extra[0])
+             && finite(p->extra[1]) && finite(p->extra[2])))
+        return fail(SANS_E_INVALID_ARG, "core-shell parallelepiped: slab thicknesses extra[0..2] must be >= 0");
     if (p->kind == SANS_CORE_SHELL_CYLINDER && !(p->extra[0] >= 0.0 && finite(p->extra[0])))
         return fail(SANS_E_INVALID_ARG, "core-shell cylinder: face shell extra[0] must be >= 0");
     if (p->kind == SANS_HOLLOW_CYLINDER && !(p->shell > 0.0 && finite(p->shell)))
@@ -1338,9 +1366,20 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
             a.si_e = std::tgamma(d + 1.0);
         }
     }
-    if (p->kind == SANS_CORE_SHELL_CYLINDER) {
+    if (p->kind == SANS_CORE_SHELL_CYLINDER || p->kind == SANS_CORE_SHELL_BICELLE) {
         a.cs_face = p->extra[0];
         a.fcs_face = (float)p->extra[0];
+    }
+    if (p->kind == SANS_CORE_SHELL_BICELLE) {
+        a.bi_c[0] = (float)(p->sld[0] - p->extra[1]);
+        a.bi_c[1] = (float)(p->extra[1] - p->sld[1]);
+        a.bi_c[2] = (float)(p->sld[1] - p->sld[2]);
+    }
+    if (p->kind == SANS_CORE_SHELL_PARALLELEPIPED) {
+        for (int k = 0; k < 3; ++k) {
+            a.csp_t[k] = p->extra[k];
+            a.fcsp_t[k] = (float)p->extra[k];
+        }
     }
     if (is_shape_independent(p->kind)) {
         a.si_scale = (float)p->extra[0];
@@ -1561,7 +1600,8 @@ int configure(sans_model_s* m, const sans_params* p)
                                   && p->size[0] == p->size[1]
                                   && ((p->poly_mask & 1) != 0) == ((p->poly_mask & 2) != 0);
             dims = (p->kind == SANS_CYLINDER || p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER
-                    || p->kind == SANS_HOLLOW_CYLINDER || p->kind == SANS_CORE_SHELL_CYLINDER || spheroid)
+                    || p->kind == SANS_HOLLOW_CYLINDER || p->kind == SANS_CORE_SHELL_CYLINDER
+                    || p->kind == SANS_CORE_SHELL_BICELLE || spheroid)
                        ? 1 : 2;
         }
         a.quad_n = n;

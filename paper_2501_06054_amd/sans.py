@@ -33,7 +33,8 @@ KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelep
         "fuzzy_sphere": 25, "vesicle": 26, "multilayer_vesicle": 27, "linear_pearls": 28,
         "surface_fractal": 29, "two_power_law": 30, "guinier_porod": 31, "spinodal": 32, "porod": 33,
         "line": 34, "two_lorentzian": 35, "correlation_length": 36, "broad_peak": 37, "fractal": 38,
-        "fractal_core_shell": 39, "polymer_excl_volume": 40}
+        "fractal_core_shell": 39, "polymer_excl_volume": 40, "elliptical_cylinder": 41,
+        "core_shell_bicelle": 42, "core_shell_parallelepiped": 43}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 POLY_KIND = {"schulz": 0, "gaussian": 1}

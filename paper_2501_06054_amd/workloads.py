@@ -29,7 +29,8 @@ KINDS = ("sphere", "core_shell", "cylinder", "ellipsoid", "parallelepiped")
 #: polymer micelle (Tables I-II)
 EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle", "hollow_cylinder",
                "core_shell_cylinder", "core_shell_ellipsoid", "hollow_prism_thick", "fuzzy_sphere",
-               "vesicle", "multilayer_vesicle", "linear_pearls", "fractal", "fractal_core_shell")
+               "vesicle", "multilayer_vesicle", "linear_pearls", "fractal", "fractal_core_shell",
+               "elliptical_cylinder", "core_shell_bicelle", "core_shell_parallelepiped")
 #: shape-independent models: a cross-section in 1/cm, extra[0] = I(0)
 SHAPE_INDEPENDENT_KINDS = ("guinier", "ornstein_zernike", "dab", "gauss_coil", "poly_gauss_coil",
                            "teubner_strey", "power_law", "gaussian_peak", "lorentz_peak", "mass_fractal",
@@ -270,6 +271,16 @@ def polymer_excl_volume() -> dict:
                               nx=256, ny=256))
 
 
+def oriented_elliptical_cylinder() -> dict:
+    """Elliptical cylinders (semi-axes 15 and 40 A, length 300 A) with the
+    axis along x and Gaussian spread 10 deg on all three angles, 256x256,
+    1e9 neutrons."""
+    return dict(name="oriented_elliptical_cylinder", n=10**9, seed=22, exp_id=0,
+                params=params(kind="elliptical_cylinder", size=(15.0, 40.0, 300.0), sld=(1e-6, 0, 0),
+                              phi=0.01, orient_kind="gaussian", orient_mean=(90 * DEG, 0.0, 0.0),
+                              orient_sigma=(10 * DEG, 10 * DEG, 10 * DEG), nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -291,6 +302,7 @@ WORKLOADS = {
     "mass_fractal": mass_fractal,
     "multilayer_vesicle": multilayer_vesicle,
     "polymer_excl_volume": polymer_excl_volume,
+    "oriented_elliptical_cylinder": oriented_elliptical_cylinder,
 }
 
 

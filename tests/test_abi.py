@@ -140,6 +140,11 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
     (dict(kind="broad_peak", size=(10.0, -0.1, 0.0), extra=(1.0, 2.0, 1.0, 2.0)), "SANS_E_INVALID_ARG"),
     (dict(kind="fractal", size=(10.0, 100.0, 0.0), extra=(0.0, 3.5, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
     (dict(kind="polymer_excl_volume", size=(10.0, 0.0, 0.0), extra=(1.0, 0.2, 0.0, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="elliptical_cylinder", size=(10.0, 20.0, 0.0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="core_shell_bicelle", size=(10.0, 20.0, 0.0), shell=2.0, extra=(-1.0, 1e-6, 0, 0)),
+     "SANS_E_INVALID_ARG"),
+    (dict(kind="core_shell_parallelepiped", size=(10.0, 20.0, 30.0), extra=(1.0, -1.0, 1.0, 0)),
+     "SANS_E_INVALID_ARG"),
 ])
 def test_capped_body_params_rejected_without_gpu(S, over, code):
     from paper_2501_06054_amd import workloads as W
@@ -151,6 +156,6 @@ def test_capped_body_params_rejected_without_gpu(S, over, code):
 def test_unknown_kind_rejected_without_gpu(S):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=1.0))
-    sp.kind = 41
+    sp.kind = 44
     h = C.c_void_p()
     assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED

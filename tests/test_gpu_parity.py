@@ -255,6 +255,20 @@ PER_NEUTRON = {
     "polymer_excl_volume": (W.workload("polymer_excl_volume")["params"], 50021),
     "polymer_excl_volume_compact": (W.params(kind="polymer_excl_volume", size=(150.0, 0, 0),
                                              extra=(3.0, 0.34, 0, 0)), 30011),
+    # oriented: elliptical cylinder, bicelle, core-shell box
+    "oriented_elliptical_cylinder": (W.workload("oriented_elliptical_cylinder")["params"], 50021),
+    "quad_elliptical_cylinder": (W.params(kind="elliptical_cylinder", mode="quad", size=(15, 40, 150),
+                                          orient_kind="isotropic"), 601),
+    "bicelle_poly_iso": (W.params(kind="core_shell_bicelle", size=(30, 40, 0), shell=8.0,
+                                  sld=(1e-6, 4e-6, 6.3e-6), extra=(6.0, 2.5e-6, 0, 0), poly=0.15, poly_mask=3,
+                                  orient_kind="isotropic"), 30011),
+    "quad_bicelle": (W.params(kind="core_shell_bicelle", mode="quad", size=(30, 40, 0), shell=8.0,
+                              sld=(1e-6, 4e-6, 6.3e-6), extra=(6.0, 2.5e-6, 0, 0), orient_kind="isotropic"),
+                     601),
+    "cs_parallelepiped_gauss": (W.params(kind="core_shell_parallelepiped", size=(30, 50, 90),
+                                         sld=(1e-6, 3e-6, 6.3e-6), extra=(4.0, 6.0, 3.0, 0),
+                                         orient_kind="gaussian", orient_mean=(0.5, 1.0, 0.2),
+                                         orient_sigma=(0.2, 0.2, 0.2)), 30011),
 }
 
 
@@ -282,7 +296,8 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "oriented_core_shell_cylinder", "iso_poly_hollow_cylinder", "iso_core_shell_ellipsoid",
              "oriented_hollow_prism_thick", "teubner_strey", "poly_gauss_coil", "dab", "mass_fractal",
              "star_polymer", "gaussian_peak", "multilayer_vesicle", "linear_pearls_poly", "spinodal",
-             "fractal_poly", "polymer_excl_volume", "broad_peak"]
+             "fractal_poly", "polymer_excl_volume", "broad_peak", "oriented_elliptical_cylinder",
+             "bicelle_poly_iso", "cs_parallelepiped_gauss"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -315,7 +330,8 @@ def test_quad_detector_parity(S, name):
 def test_pq_avg_matches_oracle(S):
     for name in ("quad_parallelepiped", "quad_spheroid", "quad_coreshell", "quad_capped_cylinder",
                  "quad_hollow_prism", "quad_micelle_poly", "quad_hollow_cylinder",
-                 "quad_core_shell_spheroid_poly", "quad_hollow_prism_thick", "quad_linear_pearls"):
+                 "quad_core_shell_spheroid_poly", "quad_hollow_prism_thick", "quad_linear_pearls",
+                 "quad_elliptical_cylinder", "quad_bicelle"):
         p, _ = PER_NEUTRON[name]
         m = S.Model(p)
         qs = np.concatenate([np.linspace(0.0, 0.06, 61), np.geomspace(1e-4, 0.3, 40)])
