@@ -65,7 +65,10 @@ typedef struct {
                               fractal aggregates of spheres: 38 homogeneous,
                               39 core-shell; oriented: 41 elliptical
                               cylinder, 42 core-shell bicelle, 43 core-shell
-                              parallelepiped                                */
+                              parallelepiped, 44 elliptical core-shell
+                              bicelle, 45 stacked disks, 46 simple cubic,
+                              47 body-centred, 48 face-centred cubic
+                              paracrystals of spheres                       */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -559,6 +562,29 @@ static double amplitude(int kind, const double s[3], double shell, const double 
              + (rf - sld[1]) * cyl_amp(s[0], s[1] + 2.0 * tf, qab, qc)
              + (sld[1] - sld[2]) * cyl_amp(s[0] + shell, s[1] + 2.0 * tf, qab, qc);
     }
+    case 44: { /* elliptical core-shell bicelle: the bicelle with its cross
+                  sections stretched by extra[2] along B (the core's semi-axes
+                  R and x R; the rim adds shell to both) */
+        double xr = extra[2], tf = extra[0], rf = extra[1], rr = s[0] + shell;
+        double a1 = sqrt((s[0] * qa) * (s[0] * qa) + (xr * s[0] * qb) * (xr * s[0] * qb));
+        double a2 = sqrt((rr * qa) * (rr * qa) + ((xr * s[0] + shell) * qb) * ((xr * s[0] + shell) * qb));
+        double lf = s[1] + 2.0 * tf;
+        double core = ORC_PI * s[0] * xr * s[0] * s[1] * orc_sinc(0.5 * qc * s[1]) * orc_lambda1(a1);
+        double faces = ORC_PI * s[0] * xr * s[0] * lf * orc_sinc(0.5 * qc * lf) * orc_lambda1(a1);
+        double outer = ORC_PI * rr * (xr * s[0] + shell) * lf * orc_sinc(0.5 * qc * lf) * orc_lambda1(a2);
+        return (sld[0] - rf) * core + (rf - sld[1]) * faces + (sld[1] - sld[2]) * outer;
+    }
+    case 45: { /* one disk of the stack: a core of radius R, thickness s1, with
+                  layers of thickness shell on both faces */
+        double qab2 = q * q - qc * qc;
+        double qab = qab2 > 0.0 ? sqrt(qab2) : 0.0;
+        return (sld[0] - sld[1]) * cyl_amp(s[0], s[1], qab, qc)
+             + (sld[1] - sld[2]) * cyl_amp(s[0], s[1] + 2.0 * shell, qab, qc);
+    }
+    case 46:
+    case 47:
+    case 48: /* the lattice's sphere, radius s0 */
+        return drho * vol_sphere(s[0]) * orc_sph(q * s[0]);
     case 43: { /* core-shell parallelepiped: the core box and, on each pair of
                   faces, a slab of thickness extra[k] covering just that face
                   (SLD sld[1]); the two slabs normal to an axis sit at +-(edge +
@@ -803,6 +829,46 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
     if (shape_independent(p->kind)) return shape_independent_iq(p, s, q);
     if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
     if (p->kind >= 25 && p->kind <= 28) return sphere_family_f2(p, s, q);
+    if (p->kind == 45) {
+        /* stacked disks: N = extra[0] disks, spacing d = s1 + 2 shell along C with
+           Gaussian spread extra[1]: F^2 times 1 + (2/N) sum_k (N - k) cos(k d Q_C)
+           exp(-k (Q_C sigma)^2 / 2) */
+        double f = amplitude(p->kind, s, p->shell, p->sld, p->extra, q, qa, qb, qc, p->quad_n);
+        int n = (int)p->extra[0];
+        double d = s[1] + 2.0 * p->shell, sg = p->extra[1], st = 1.0;
+        for (int k = 1; k < n; ++k)
+            st += 2.0 / n * (n - k) * cos(k * d * qc) * exp(-0.5 * k * qc * qc * sg * sg);
+        return f * f * st;
+    }
+    if (p->kind >= 46 && p->kind <= 48) {
+        /* paracrystals (Matsuoka): spheres on a cubic lattice whose primitive
+           vectors a_k (nearest-neighbour distance D = s1) are the particle axes'
+           combinations; each direction a one-dimensional paracrystal with
+           Gaussian distortion g D: Z_k = (1 - e^2) / (1 - 2 e cos(Q.a_k) + e^2),
+           e = exp(-(q g D)^2 / 2); the lattice factor is the product */
+        double f = amplitude(p->kind, s, p->shell, p->sld, p->extra, q, qa, qb, qc, p->quad_n);
+        double dd = s[1], e = exp(-0.5 * q * q * p->extra[0] * p->extra[0] * dd * dd);
+        double v[3][3];
+        if (p->kind == 46) {          /* simple cubic: a = D */
+            double b[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+            memcpy(v, b, sizeof(v));
+            for (int k = 0; k < 3; ++k) for (int j = 0; j < 3; ++j) v[k][j] *= dd;
+        } else if (p->kind == 47) {   /* bcc: a = 2 D / sqrt 3, vectors (a/2)(-1,1,1) ... */
+            double b[3][3] = {{-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
+            memcpy(v, b, sizeof(v));
+            for (int k = 0; k < 3; ++k) for (int j = 0; j < 3; ++j) v[k][j] *= dd / sqrt(3.0);
+        } else {                      /* fcc: a = sqrt 2 D, vectors (a/2)(0,1,1) ... */
+            double b[3][3] = {{0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+            memcpy(v, b, sizeof(v));
+            for (int k = 0; k < 3; ++k) for (int j = 0; j < 3; ++j) v[k][j] *= dd / sqrt(2.0);
+        }
+        double z = 1.0;
+        for (int k = 0; k < 3; ++k) {
+            double x = qa * v[k][0] + qb * v[k][1] + qc * v[k][2];
+            z *= (1.0 - e * e) / (1.0 - 2.0 * e * cos(x) + e * e);
+        }
+        return f * f * z;
+    }
     if (p->kind == 38 || p->kind == 39) {
         /* blocks: a sphere (38) or a core-shell sphere (39) of radius size[0]
            (core), shell; fractal: xi = size[1], D = extra[1] */
@@ -816,7 +882,7 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
 }
 
 /* Orientation matters (the particles from 2 to 12 but the micelle). */
-static int anisotropic(int kind) { return (kind >= 2 && kind != 8 && kind <= 12) || (kind >= 41 && kind <= 43); }
+static int anisotropic(int kind) { return (kind >= 2 && kind != 8 && kind <= 12) || (kind >= 41 && kind <= 48); }
 
 /* Sizes scaled by the relative size draw y according to the mask. */
 static void scaled_sizes(const orc_params* p, double y, double s[3])
@@ -947,6 +1013,21 @@ double orc_mean_volume(const orc_params* p)
         int bb[3] = {b0, b1, b2};
         return 4.0 / 3.0 * ORC_PI * prod_moment(p, s, be, bb, 3);
     }
+    case 44: { /* the outer elliptic cylinder pi (R + t)(x R + t)(L + 2 t_f) */
+        double xr = p->extra[2];
+        double al[3] = {s[0], xr * s[0], s[1]}, be[3] = {p->shell, p->shell, 2.0 * p->extra[0]};
+        int bb[3] = {b0, b0, b1};
+        return ORC_PI * prod_moment(p, al, be, bb, 3);
+    }
+    case 45: { /* one disk: pi R^2 (core + two layers) */
+        double al[3] = {s[0], s[0], s[1]}, be[3] = {0.0, 0.0, 2.0 * p->shell};
+        int bb[3] = {b0, b0, b1};
+        return ORC_PI * prod_moment(p, al, be, bb, 3);
+    }
+    case 46:
+    case 47:
+    case 48:
+        return vol_sphere(s[0]) * size_moment(p, b0 ? 3 : 0);
     case 41: /* pi a b L */
         return ORC_PI * s[0] * s[1] * s[2] * size_moment(p, b0 + b1 + b2);
     case 42: { /* the outer cylinder pi (R y^b0 + t)^2 (L y^b1 + 2 t_f) */
@@ -1088,7 +1169,7 @@ static double pq_avg_nodes(const orc_params* p, double q, const double qvec[3],
     int iso = aniso && p->orient_kind == 2;
     /* a spheroid (a = b, scaled alike) needs only the angle to its C axis */
     int one_axis = (p->kind == 2 || p->kind == 5 || p->kind == 6 || p->kind == 9 || p->kind == 10
-                    || p->kind == 42)
+                    || p->kind == 42 || p->kind == 45)
                 || ((p->kind == 3 || p->kind == 11) && p->size[0] == p->size[1]
                     && (p->poly_mask & 1) == (p->poly_mask >> 1 & 1));
     double A[3], B[3], C[3];

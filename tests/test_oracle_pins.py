@@ -1336,3 +1336,94 @@ def test_oriented_mean_volume_by_quadrature(orc, kind, size, shell, extra, mask)
     vol = lambda y: orc.amplitude(mono, 0.0, (0.0, 0.0, 0.0), y, (0.0, 0.0, 0.0)) * pdf(y)
     ref, _ = integrate.quad(vol, 0.0, 4.0, limit=200, epsabs=0.0, epsrel=1e-12)
     assert orc.mean_volume(p) == pytest.approx(ref, rel=1e-9)
+
+
+# ------------------------------------------------------------------ elliptical bicelle, stacked disks, paracrystals
+
+@pytest.mark.parametrize("qv", [(0.0, 0.0, 0.0), (0.03, 0.0, 0.0), (0.0, 0.04, 0.01), (0.02, -0.03, 0.05)])
+def test_elliptical_bicelle_is_its_layers(orc, qv):
+    R, xr, L, t, tf = 20.0, 1.8, 50.0, 6.0, 5.0
+    rc, rr, rs, rf = 1.0e-6, 4.0e-6, 6.3e-6, 2.5e-6
+    p = W.params(kind="core_shell_bicelle_elliptical", size=(R, L, 0), shell=t, sld=(rc, rr, rs),
+                 extra=(tf, rf, xr, 0))
+    q = math.sqrt(sum(x * x for x in qv))
+    got = orc.amplitude(p, q, qv, 1.0, (0.0, 0.0, 0.0))
+    core = _ellcyl_ft(R, xr * R, L, qv)
+    inner = _ellcyl_ft(R, xr * R, L + 2 * tf, qv)
+    outer = _ellcyl_ft(R + t, xr * R + t, L + 2 * tf, qv)
+    ref = (rc - rs) * core + (rf - rs) * (inner - core) + (rr - rs) * (outer - inner)
+    assert got == pytest.approx(ref, rel=1e-9, abs=1e-12 * math.pi * R * R * L * 1e-6)
+    # a circular section: the bicelle
+    pc = dict(p, extra=(tf, rf, 1.0, 0))
+    bc = W.params(kind="core_shell_bicelle", size=(R, L, 0), shell=t, sld=(rc, rr, rs), extra=(tf, rf, 0, 0))
+    assert orc.amplitude(pc, q, qv, 1.0, (0.4, 0.7, 0.0)) == pytest.approx(
+        orc.amplitude(bc, q, qv, 1.0, (0.4, 0.7, 0.0)), rel=1e-12, abs=1e-20)
+
+
+def test_stacked_disks_single_disk_and_stack_disorder(orc):
+    """One disk is the core-shell cylinder without a rim; the stack factor is
+    the average over stacks whose spacings scatter as N(d, sigma^2) each (the
+    disorder accumulates), here by simulation."""
+    R, Lc, tl = 60.0, 20.0, 8.0
+    sld = (1e-6, 4e-6, 6.3e-6)
+    one = W.params(kind="stacked_disks", size=(R, Lc, 0), shell=tl, sld=sld, extra=(1.0, 5.0, 0, 0))
+    csc = W.params(kind="core_shell_cylinder", size=(R, Lc, 0), shell=0.0, sld=sld, extra=(tl, 0, 0, 0))
+    for qv in ((0.0, 0.0, 0.02), (0.01, 0.0, 0.03)):
+        q = math.sqrt(sum(x * x for x in qv))
+        assert orc.form_f2(one, q, qv, 1.0, (0, 0, 0)) == pytest.approx(
+            orc.amplitude(csc, q, qv, 1.0, (0, 0, 0)) ** 2, rel=1e-12)
+    n, sig = 6, 4.0
+    d = Lc + 2 * tl
+    stack = dict(one, extra=(float(n), sig, 0, 0))
+    rng = np.random.default_rng(3)
+    gaps = d + sig * rng.standard_normal((400000, n - 1))
+    z = np.concatenate([np.zeros((gaps.shape[0], 1)), np.cumsum(gaps, axis=1)], axis=1)
+    for qc in (0.02, 0.08, 0.16):
+        mc = np.mean(np.abs(np.exp(1j * qc * z).sum(1)) ** 2) / n
+        f2 = orc.amplitude(csc, qc, (0.0, 0.0, qc), 1.0, (0, 0, 0)) ** 2
+        got = orc.form_f2(stack, qc, (0.0, 0.0, qc), 1.0, (0, 0, 0)) / f2
+        assert got == pytest.approx(mc, rel=2e-2, abs=2e-3)
+
+
+def _paracrystal_factor(x, e, nmax=4000):
+    """sum_n e^|n| exp(i n x): the one-dimensional paracrystal's lattice factor."""
+    n = np.arange(1, nmax)
+    return 1.0 + 2.0 * np.sum(e ** n * np.cos(n * x))
+
+
+@pytest.mark.parametrize("kind", ["sc_paracrystal", "bcc_paracrystal", "fcc_paracrystal"])
+def test_paracrystal_factor_and_reflections(orc, kind):
+    R, D, g = 15.0, 60.0, 0.06
+    p = W.params(kind=kind, size=(R, D, 0), sld=(1e-6, 0, 0), extra=(g, 0, 0, 0))
+    sph = W.params(kind="sphere", size=(R, 0, 0), sld=(1e-6, 0, 0))
+    # primitive vectors (columns of the particle frame) and the cubic cell
+    if kind == "sc_paracrystal":
+        vecs, a = np.eye(3) * D, D
+        allowed, forbidden = [(1, 0, 0), (1, 1, 0), (1, 1, 1)], []
+    elif kind == "bcc_paracrystal":
+        vecs, a = np.array([[-1, 1, 1], [1, -1, 1], [1, 1, -1]]) * D / math.sqrt(3), 2 * D / math.sqrt(3)
+        allowed, forbidden = [(1, 1, 0), (2, 0, 0)], [(1, 0, 0), (1, 1, 1)]
+    else:
+        vecs, a = np.array([[0, 1, 1], [1, 0, 1], [1, 1, 0]]) * D / math.sqrt(2), math.sqrt(2) * D
+        allowed, forbidden = [(1, 1, 1), (2, 0, 0)], [(1, 0, 0), (1, 1, 0)]
+    assert np.allclose(np.linalg.norm(vecs, axis=1), D)
+    for qv in ((0.01, 0.02, -0.03), (0.05, 0.0, 0.01)):
+        qv = np.array(qv)
+        q = float(np.linalg.norm(qv))
+        e = math.exp(-0.5 * (q * g * D) ** 2)
+        z = np.prod([_paracrystal_factor(float(qv @ v), e) for v in vecs])
+        ref = orc.amplitude(sph, q, tuple(qv)) ** 2 * z
+        assert orc.form_f2(p, q, tuple(qv), 1.0, (0, 0, 0)) == pytest.approx(ref, rel=1e-9)
+    # reciprocal lattice vectors of the cubic cell: the lattice factor peaks on
+    # the allowed reflections and stays small on the extinct ones
+    for hkl in allowed:
+        qv = 2 * math.pi / a * np.array(hkl, float)
+        q = float(np.linalg.norm(qv))
+        zr = orc.form_f2(p, q, tuple(qv), 1.0, (0, 0, 0)) / orc.amplitude(sph, q, tuple(qv)) ** 2
+        e = math.exp(-0.5 * (q * g * D) ** 2)
+        assert zr == pytest.approx(((1 + e) / (1 - e)) ** 3, rel=1e-9)
+    for hkl in forbidden:
+        qv = 2 * math.pi / a * np.array(hkl, float)
+        q = float(np.linalg.norm(qv))
+        zr = orc.form_f2(p, q, tuple(qv), 1.0, (0, 0, 0)) / orc.amplitude(sph, q, tuple(qv)) ** 2
+        assert zr < 1.0
