@@ -81,6 +81,7 @@ STEP = {
     "mfrac_I":       ((40,  0,  0,  1, 4, 0), 60),  # mass fractal: atan, sin, log2, exp2, reciprocal
     "shell_F":       ((32,  0,  0,  8, 0, 0), 44),  # one vesicle shell: two 3 j1(x)/x (FP64 phases), volumes
     "ellcyl_F":      ((24,  0,  0, 15, 0, 1), 39),  # elliptical cylinder: |(a Q_A, b Q_B)| (sqrt), sinc, 2 J1(x)/x
+    "paracrystal_Z": ((54,  6,  0, 60, 1, 3), 60),  # 3 x (Q.v_k, FP64 half-phase reduction, sin^2, quotient), e
     "pev_I":         ((2,   0,  0, 500, 0, 3), 0),  # excluded-volume chain: two FP64 incomplete gammas (~30 series
                                                     # or continued-fraction steps of 4 ops each, exp, log)
     "py_sq":         ((15,  0,  0,  0, 1, 0), 25),  # A10: series in x^2, 1/(1 + 24 phi G/x)
@@ -124,6 +125,8 @@ PATHS = {
     "polymer_excl_volume": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["pev_I"],
     "oriented_elliptical_cylinder": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
                                     + ["qvec"] + ["orient_angle"] * 3 + ["project_abc", "ellcyl_F"],
+    "oriented_fcc_paracrystal": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
+                                + ["qvec"] + ["orient_angle"] * 3 + ["project_abc", "sphere_F", "paracrystal_Z"],
 }
 # Exact-average paths, per quadrature node (76 x 76 = 5776 nodes per neutron),
 # all FP32:

@@ -157,9 +157,22 @@ typedef enum {
                                     layers of thickness extra[0] (SLD extra[1])
                                     on the ends; a rim of thickness shell (SLD
                                     sld[1]) around core and faces; axis C       */
-    SANS_CORE_SHELL_PARALLELEPIPED = 43 /* core edges size[0..2]; on each pair of
+    SANS_CORE_SHELL_PARALLELEPIPED = 43, /* core edges size[0..2]; on each pair of
                                     faces a slab of thickness extra[0..2] that
                                     covers just that face, SLD sld[1]          */
+    SANS_CORE_SHELL_BICELLE_ELLIPTICAL = 44, /* the bicelle with core semi-axes
+                                    size[0] (A) and extra[2] size[0] (B); the
+                                    rim adds shell to both                     */
+    SANS_STACKED_DISKS = 45,     /* extra[0] (integer) disks along C: core radius
+                                    size[0], thickness size[1], face layers shell
+                                    (SLD sld[1]); spacing spread extra[1] (A),
+                                    accumulating                               */
+    SANS_SC_PARACRYSTAL = 46,    /* spheres of radius size[0] on a simple cubic
+                                    paracrystal, nearest neighbours size[1],
+                                    distortion factor extra[0] in (0, 1); the
+                                    cubic axes along A, B, C                   */
+    SANS_BCC_PARACRYSTAL = 47,   /* the same, body-centred cubic               */
+    SANS_FCC_PARACRYSTAL = 48    /* the same, face-centred cubic               */
 } sans_kind;
 
 /* How the particle size and orientation enter the weight. */

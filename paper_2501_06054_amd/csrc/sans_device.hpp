@@ -127,6 +127,9 @@ struct TraceArgs {
     float bi_c[3];
     double csp_t[3];
     float fcsp_t[3];
+    // elliptical bicelle: cross-section ratio; stacked disks: spacing d, spread
+    // sigma, count (sf_n); paracrystals: primitive vectors (A), (g D)^2 / 2
+    double bi_x, sd_d, sd_sig, pc_v[3][3], pc_b;
     // run
     uint64_t first, n;
     uint32_t seed_lo, seed_hi, exp_id;
@@ -494,7 +497,13 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kSurfaceFractal = 29, kTwoPowerLaw = 30, kGuinierPorod = 31, kSpinodal = 32, kPorod = 33,
               kLine = 34, kTwoLorentzian = 35, kCorrelationLength = 36, kBroadPeak = 37, kFractal = 38,
               kFractalCoreShell = 39, kPolymerExclVolume = 40, kEllipticalCylinder = 41,
-              kCoreShellBicelle = 42, kCoreShellParallelepiped = 43 };
+              kCoreShellBicelle = 42, kCoreShellParallelepiped = 43, kCoreShellBicelleElliptical = 44,
+              kStackedDisks = 45, kScParacrystal = 46, kBccParacrystal = 47, kFccParacrystal = 48 };
+
+// F^2 multiplied by an orientation-dependent interference factor (stacked
+// disks, paracrystals).
+template <int KIND>
+constexpr bool kLattice = KIND >= kStackedDisks && KIND <= kFccParacrystal;
 
 // Shape-independent models: the weight is a cross-section in 1/cm of |Q|.
 template <int KIND>
@@ -512,14 +521,15 @@ constexpr bool kSphereFamily = (KIND >= kFuzzySphere && KIND <= kLinearPearls) |
 // thick hollow prism, but the micelle).
 template <int KIND>
 constexpr bool kAniso = (KIND >= kCylinder && KIND <= kHollowPrismThick && KIND != kMicelle)
-                        || (KIND >= kEllipticalCylinder && KIND <= kCoreShellParallelepiped);
+                        || (KIND >= kEllipticalCylinder && KIND <= kFccParacrystal);
 
 // Bodies of revolution about C: cylinders (plain, hollow, core-shell),
 // barbell, capped cylinder (only the axis projection Q.C and Q_AB enter, the
 // third angle does not).
 template <int KIND>
 constexpr bool kOneAxis = KIND == kCylinder || KIND == kBarbell || KIND == kCappedCylinder
-                          || KIND == kHollowCylinder || KIND == kCoreShellCylinder || KIND == kCoreShellBicelle;
+                          || KIND == kHollowCylinder || KIND == kCoreShellCylinder || KIND == kCoreShellBicelle
+                          || KIND == kStackedDisks;
 
 // The caps' part of the barbell / capped-cylinder amplitude (Tables I-II,
 // group A), in FP32: sum_i w_i cos(P + B t_i) 2J1(X s_i)/(X s_i) over the
@@ -836,6 +846,42 @@ __device__ __forceinline__ float sphere_family_f2(const TraceArgs& a, double R, 
     }
 }
 
+// Interference factors multiplying F^2 (FP64 phases):
+// stacked disks: 1 + (2/N) sum_k (N - k) cos(k d Q_C) exp(-k (Q_C sigma)^2 / 2)
+// (spacings scattering as N(d, sigma^2) each, the disorder accumulating);
+// paracrystals (Matsuoka): the product over the three primitive vectors v_k
+// of (1 - e^2) / ((1 - e)^2 + 4 e sin^2(Q.v_k / 2)), e = exp(-(q g D)^2 / 2)
+// (the same as (1 - e^2)/(1 - 2e cos + e^2), without its cancellation).
+template <int KIND>
+__device__ __forceinline__ float lattice_factor(const TraceArgs& a, double q, double qa, double qb, double qc)
+{
+    if constexpr (KIND == kStackedDisks) {
+        const int n = a.sf_n;
+        const float damp = (float)exp(-0.5 * qc * qc * a.sd_sig * a.sd_sig);
+        float s = 0.0f, dk = 1.0f;
+        for (int k = 1; k < n; ++k) {
+            float sv, cv;
+            sincos_phase(qc * (k * a.sd_d), sv, cv);
+            dk *= damp;
+            s = __builtin_fmaf((float)(n - k) * dk, cv, s);
+        }
+        return 1.0f + 2.0f * s / (float)n;
+    } else {
+        const double b = q * q * a.pc_b;
+        const double ome = -expm1(-b), e = exp(-b);
+        float z = 1.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double x = qa * a.pc_v[k][0] + qb * a.pc_v[k][1] + qc * a.pc_v[k][2];
+            float sh, ch;
+            sincos_phase(0.5 * x, sh, ch);
+            const double den = __builtin_fma(4.0 * e, (double)sh * (double)sh, ome * ome);
+            z *= (float)(ome * (1.0 + e) / den);
+        }
+        return z;
+    }
+}
+
 // F of one drawn particle (MC mode).  y scales the sizes selected by the
 // polydispersity mask; q, qa, qb, qc are |Q| and its projections (FP64).
 template <int KIND>
@@ -928,6 +974,28 @@ __device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, doub
         const float faces = r * r * flf * ends * disc;
         const float outer = fro * fro * flf * ends * lambda1_f((float)(qab * ro));
         return (float)kPi * (a.bi_c[0] * core + a.bi_c[1] * faces + a.bi_c[2] * outer);
+    } else if constexpr (KIND == kCoreShellBicelleElliptical) {
+        // cross sections R x xR (core, faces) and (R + rim) x (xR + rim) (outer)
+        const double ra = s[0], rb = a.bi_x * s[0], oa = ra + a.shell, ob = rb + a.shell;
+        const double lf = __builtin_fma(2.0, a.cs_face, s[1]);
+        const float d1 = lambda1_f((float)sqrt((ra * qa) * (ra * qa) + (rb * qb) * (rb * qb)));
+        const float d2 = lambda1_f((float)sqrt((oa * qa) * (oa * qa) + (ob * qb) * (ob * qb)));
+        const float ends = sinc_d(0.5 * qc * lf);
+        const float core = (float)ra * (float)rb * (float)s[1] * sinc_d(0.5 * qc * s[1]) * d1;
+        const float faces = (float)ra * (float)rb * (float)lf * ends * d1;
+        const float outer = (float)oa * (float)ob * (float)lf * ends * d2;
+        return (float)kPi * (a.bi_c[0] * core + a.bi_c[1] * faces + a.bi_c[2] * outer);
+    } else if constexpr (KIND == kStackedDisks) {
+        // one disk: core (R, s1) and core + face layers (R, s1 + 2 shell)
+        const double qab = sqrt(fmax(__builtin_fma(q, q, -qc * qc), 0.0));
+        const double lo = __builtin_fma(2.0, a.shell, s[1]);
+        const float r = (float)s[0], disc = lambda1_f((float)(qab * s[0]));
+        const float core = r * r * (float)s[1] * sinc_d(0.5 * qc * s[1]) * disc;
+        const float outer = r * r * (float)lo * sinc_d(0.5 * qc * lo) * disc;
+        return (float)kPi * __builtin_fmaf(a.cs_core, core, a.cs_shell * outer);
+    } else if constexpr (KIND == kScParacrystal || KIND == kBccParacrystal || KIND == kFccParacrystal) {
+        const float r = (float)s[0];
+        return a.contrast * k43pi * r * r * r * sph3j_d(q * s[0]);
     } else if constexpr (KIND == kCoreShellParallelepiped) {
         // the core box and the face slabs, each pair 2 cos(Q (edge + t)/2) times one slab
         const float A = (float)s[0], B = (float)s[1], C = (float)s[2];
@@ -1020,6 +1088,25 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
         const float faces = r * r * lf * ends * disc;
         const float outer = ro * ro * lf * ends * lambda1_f(qab * ro);
         return (float)kPi * (a.bi_c[0] * core + a.bi_c[1] * faces + a.bi_c[2] * outer);
+    } else if constexpr (KIND == kCoreShellBicelleElliptical) {
+        const float ra = s[0], rb = (float)a.bi_x * s[0], oa = ra + a.fshell, ob = rb + a.fshell;
+        const float lf = __builtin_fmaf(2.0f, a.fcs_face, s[1]);
+        const float xa1 = ra * qa, xb1 = rb * qb, xa2 = oa * qa, xb2 = ob * qb;
+        const float d1 = lambda1_f(sqrtf(__builtin_fmaf(xa1, xa1, xb1 * xb1)));
+        const float d2 = lambda1_f(sqrtf(__builtin_fmaf(xa2, xa2, xb2 * xb2)));
+        const float ends = sinc_f(0.5f * qc * lf);
+        const float core = ra * rb * s[1] * sinc_f(0.5f * qc * s[1]) * d1;
+        const float faces = ra * rb * lf * ends * d1;
+        const float outer = oa * ob * lf * ends * d2;
+        return (float)kPi * (a.bi_c[0] * core + a.bi_c[1] * faces + a.bi_c[2] * outer);
+    } else if constexpr (KIND == kStackedDisks) {
+        const float qab = sqrtf(fmaxf(__builtin_fmaf(q, q, -qc * qc), 0.0f));
+        const float r = s[0], lo = __builtin_fmaf(2.0f, a.fshell, s[1]), disc = lambda1_f(qab * r);
+        const float core = r * r * s[1] * sinc_f(0.5f * qc * s[1]) * disc;
+        const float outer = r * r * lo * sinc_f(0.5f * qc * lo) * disc;
+        return (float)kPi * __builtin_fmaf(a.cs_core, core, a.cs_shell * outer);
+    } else if constexpr (KIND == kScParacrystal || KIND == kBccParacrystal || KIND == kFccParacrystal) {
+        return a.contrast * k43pi * s[0] * s[0] * s[0] * sph3j_f(q * s[0]);
     } else if constexpr (KIND == kCoreShellParallelepiped) {
         const float A = s[0], B = s[1], C = s[2];
         const float ta = a.fcsp_t[0], tb = a.fcsp_t[1], tc = a.fcsp_t[2];
@@ -1089,6 +1176,7 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
             } else {
                 const float f = amplitude_f<KIND>(a, s, q, qa0, qb0, qc0, y);
                 f2 = f * f;
+                if constexpr (kLattice<KIND>) f2 *= lattice_factor<KIND>(a, q, qa0, qb0, qc0);
             }
             avg = i0 == 0 ? f2 : 0.0f;
         } else if (a.quad_dims == 1) {
@@ -1114,7 +1202,9 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
 #pragma unroll 4
                 for (int i = i0; i < n; i += istep) {
                     const float f = amplitude_f<KIND>(a, s, q, q * stt[i], 0.0f, q * mu[i], y);
-                    avg = __builtin_fmaf(wmu[i], f * f, avg);
+                    float f2 = f * f;
+                    if constexpr (kLattice<KIND>) f2 *= lattice_factor<KIND>(a, q, q * stt[i], 0.0f, q * mu[i]);
+                    avg = __builtin_fmaf(wmu[i], f2, avg);
                 }
             }
         } else if constexpr (KIND == kParallelepiped) {
@@ -1176,7 +1266,9 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
                 float inner = 0.0f;
                 for (int l = 0; l < n; ++l) {
                     const float f = amplitude_f<KIND>(a, s, q, qst * cb[l], qst * sb[l], qc, y);
-                    inner = __builtin_fmaf(wb[l], f * f, inner);
+                    float f2 = f * f;
+                    if constexpr (kLattice<KIND>) f2 *= lattice_factor<KIND>(a, q, qst * cb[l], qst * sb[l], qc);
+                    inner = __builtin_fmaf(wb[l], f2, inner);
                 }
                 avg = __builtin_fmaf(wmu[i], inner, avg);
             }
@@ -1335,6 +1427,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
         } else {
             const float f = amplitude_mc<KIND>(a, y, qd, qa, qb, qc);
             f2 = f * f;
+            if constexpr (kLattice<KIND>) f2 *= lattice_factor<KIND>(a, qd, qa, qb, qc);
         }
     } else if constexpr (MODE == 1) {
         const float qv[3] = {(float)qvd[0], (float)qvd[1], (float)qvd[2]};

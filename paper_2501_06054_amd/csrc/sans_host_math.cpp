@@ -278,6 +278,22 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
                       + extra[1] * size[0] * size[2] * size_moment(poly_kind, poly, k0 + k2)
                       + extra[2] * size[0] * size[1] * size_moment(poly_kind, poly, k0 + k1));
     }
+    case 44: {
+        // the outer elliptic cylinder pi (R y^b0 + t)(x R y^b0 + t)(L y^b1 + 2 t_f)
+        const double f[3][2] = {{size[0], shell}, {extra[2] * size[0], shell}, {size[1], 2.0 * extra[0]}};
+        const int k[3] = {b0 ? 1 : 0, b0 ? 1 : 0, b1 ? 1 : 0};
+        return kPiH * expand_moment(f, k, poly_kind, poly);
+    }
+    case 45: {
+        // one disk: pi R^2 (core + two layers)
+        const double f[3][2] = {{size[0], 0.0}, {size[0], 0.0}, {size[1], 2.0 * shell}};
+        const int k[3] = {b0 ? 1 : 0, b0 ? 1 : 0, b1 ? 1 : 0};
+        return kPiH * expand_moment(f, k, poly_kind, poly);
+    }
+    case 46:
+    case 47:
+    case 48:
+        return mean_volume(0, size, shell, poly, mask, poly_kind, extra);
     case 38:
         return mean_volume(0, size, shell, poly, mask, poly_kind, extra);
     case 39:

@@ -537,7 +537,12 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 40: batch_tile<40>(a, tl.first, tl.count, hist, tab); break;
         case 41: batch_tile<41>(a, tl.first, tl.count, hist, tab); break;
         case 42: batch_tile<42>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<43>(a, tl.first, tl.count, hist, tab); break;
+        case 43: batch_tile<43>(a, tl.first, tl.count, hist, tab); break;
+        case 44: batch_tile<44>(a, tl.first, tl.count, hist, tab); break;
+        case 45: batch_tile<45>(a, tl.first, tl.count, hist, tab); break;
+        case 46: batch_tile<46>(a, tl.first, tl.count, hist, tab); break;
+        case 47: batch_tile<47>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<48>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -814,6 +819,11 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(41)
         SANS_CASE(42)
         SANS_CASE(43)
+        SANS_CASE(44)
+        SANS_CASE(45)
+        SANS_CASE(46)
+        SANS_CASE(47)
+        SANS_CASE(48)
     }
 #undef SANS_CASE
     return nullptr;
@@ -872,6 +882,11 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(41)
         SANS_CASE(42)
         SANS_CASE(43)
+        SANS_CASE(44)
+        SANS_CASE(45)
+        SANS_CASE(46)
+        SANS_CASE(47)
+        SANS_CASE(48)
     }
 #undef SANS_CASE
     return nullptr;
@@ -927,6 +942,11 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(41)
         SANS_CASE(42)
         SANS_CASE(43)
+        SANS_CASE(44)
+        SANS_CASE(45)
+        SANS_CASE(46)
+        SANS_CASE(47)
+        SANS_CASE(48)
     }
 #undef SANS_CASE
     return nullptr;
@@ -982,6 +1002,11 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(41)
         SANS_CASE(42)
         SANS_CASE(43)
+        SANS_CASE(44)
+        SANS_CASE(45)
+        SANS_CASE(46)
+        SANS_CASE(47)
+        SANS_CASE(48)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1034,6 +1059,11 @@ PqFn pick_pq(int kind)
     case 41: return k_pq_avg<41>;
     case 42: return k_pq_avg<42>;
     case 43: return k_pq_avg<43>;
+    case 44: return k_pq_avg<44>;
+    case 45: return k_pq_avg<45>;
+    case 46: return k_pq_avg<46>;
+    case 47: return k_pq_avg<47>;
+    case 48: return k_pq_avg<48>;
     }
     return nullptr;
 }
@@ -1096,14 +1126,14 @@ bool is_sphere_family(int kind)
 bool is_aniso(int kind)
 {
     return (kind >= SANS_CYLINDER && kind <= SANS_HOLLOW_PRISM_THICK && kind != SANS_POLYMER_MICELLE)
-           || (kind >= SANS_ELLIPTICAL_CYLINDER && kind <= SANS_CORE_SHELL_PARALLELEPIPED);
+           || (kind >= SANS_ELLIPTICAL_CYLINDER && kind <= SANS_FCC_PARACRYSTAL);
 }
 
 int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 43) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 48) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -1118,7 +1148,9 @@ int validate(const sans_params* p)
     if (p->tally < 0 || p->tally > 4) return fail(SANS_E_UNSUPPORTED, "unknown tally strategy");
     const bool two_sizes = p->kind == SANS_CYLINDER || p->kind == SANS_POLYMER_MICELLE
                            || p->kind == SANS_HOLLOW_CYLINDER || p->kind == SANS_CORE_SHELL_CYLINDER
-                           || p->kind == SANS_CORE_SHELL_BICELLE;
+                           || p->kind == SANS_CORE_SHELL_BICELLE || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL
+                           || p->kind == SANS_STACKED_DISKS || p->kind == SANS_SC_PARACRYSTAL
+                           || p->kind == SANS_BCC_PARACRYSTAL || p->kind == SANS_FCC_PARACRYSTAL;
     int nsize = p->kind <= 1 ? 1 : (two_sizes ? 2 : 3);
     if (is_shape_independent(p->kind))
         nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK
@@ -1145,12 +1177,22 @@ int validate(const sans_params* p)
     if (p->kind == SANS_HOLLOW_PRISM && !(p->shell > 0.0 && finite(p->shell)))
         return fail(SANS_E_INVALID_ARG, "hollow prism: wall thickness (shell) must be > 0");
     if ((p->kind == SANS_CORE_SHELL_CYLINDER || p->kind == SANS_CORE_SHELL_ELLIPSOID
-         || p->kind == SANS_CORE_SHELL_BICELLE)
+         || p->kind == SANS_CORE_SHELL_BICELLE || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL
+         || p->kind == SANS_STACKED_DISKS)
         && !(p->shell >= 0.0 && finite(p->shell)))
         return fail(SANS_E_INVALID_ARG, "shell must be >= 0");
-    if (p->kind == SANS_CORE_SHELL_BICELLE
+    if ((p->kind == SANS_CORE_SHELL_BICELLE || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL)
         && !(p->extra[0] >= 0.0 && finite(p->extra[0]) && finite(p->extra[1])))
         return fail(SANS_E_INVALID_ARG, "bicelle: face thickness extra[0] >= 0 and a finite face SLD extra[1]");
+    if (p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL && !(p->extra[2] > 0.0 && finite(p->extra[2])))
+        return fail(SANS_E_INVALID_ARG, "elliptical bicelle: cross-section ratio extra[2] must be > 0");
+    if (p->kind == SANS_STACKED_DISKS
+        && !(p->extra[0] >= 1.0 && p->extra[0] <= 1000.0 && p->extra[0] == std::floor(p->extra[0])
+             && p->extra[1] >= 0.0 && finite(p->extra[1])))
+        return fail(SANS_E_INVALID_ARG, "stacked disks: integer count extra[0] in 1..1000, spread extra[1] >= 0");
+    if ((p->kind == SANS_SC_PARACRYSTAL || p->kind == SANS_BCC_PARACRYSTAL || p->kind == SANS_FCC_PARACRYSTAL)
+        && !(p->extra[0] > 0.0 && p->extra[0] < 1.0))
+        return fail(SANS_E_INVALID_ARG, "paracrystal: distortion factor extra[0] must be in (0, 1)");
     if (p->kind == SANS_CORE_SHELL_PARALLELEPIPED
         && !(p->extra[0] >= 0.0 && p->extra[1] >= 0.0 && p->extra[2] >= 0.0 && finite(p->extra[0])
              && finite(p->extra[1]) && finite(p->extra[2])))
@@ -1366,11 +1408,31 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
             a.si_e = std::tgamma(d + 1.0);
         }
     }
-    if (p->kind == SANS_CORE_SHELL_CYLINDER || p->kind == SANS_CORE_SHELL_BICELLE) {
+    if (p->kind == SANS_CORE_SHELL_CYLINDER || p->kind == SANS_CORE_SHELL_BICELLE
+        || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL) {
         a.cs_face = p->extra[0];
         a.fcs_face = (float)p->extra[0];
     }
-    if (p->kind == SANS_CORE_SHELL_BICELLE) {
+    if (p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL) a.bi_x = p->extra[2];
+    if (p->kind == SANS_STACKED_DISKS) {
+        a.sf_n = (int32_t)p->extra[0];
+        a.sd_d = p->size[1] + 2.0 * p->shell;
+        a.sd_sig = p->extra[1];
+    }
+    if (p->kind == SANS_SC_PARACRYSTAL || p->kind == SANS_BCC_PARACRYSTAL || p->kind == SANS_FCC_PARACRYSTAL) {
+        // primitive vectors in units of the nearest-neighbour distance D
+        static const double sc[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        static const double bcc[3][3] = {{-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
+        static const double fcc[3][3] = {{0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+        const double(*v)[3] = p->kind == SANS_SC_PARACRYSTAL ? sc : (p->kind == SANS_BCC_PARACRYSTAL ? bcc : fcc);
+        const double scale = p->size[1] / (p->kind == SANS_SC_PARACRYSTAL ? 1.0
+                                           : (p->kind == SANS_BCC_PARACRYSTAL ? std::sqrt(3.0) : std::sqrt(2.0)));
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 3; ++j) a.pc_v[k][j] = v[k][j] * scale;
+        const double gd = p->extra[0] * p->size[1];
+        a.pc_b = 0.5 * gd * gd;
+    }
+    if (p->kind == SANS_CORE_SHELL_BICELLE || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL) {
         a.bi_c[0] = (float)(p->sld[0] - p->extra[1]);
         a.bi_c[1] = (float)(p->extra[1] - p->sld[1]);
         a.bi_c[2] = (float)(p->sld[1] - p->sld[2]);
@@ -1601,7 +1663,7 @@ int configure(sans_model_s* m, const sans_params* p)
                                   && ((p->poly_mask & 1) != 0) == ((p->poly_mask & 2) != 0);
             dims = (p->kind == SANS_CYLINDER || p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER
                     || p->kind == SANS_HOLLOW_CYLINDER || p->kind == SANS_CORE_SHELL_CYLINDER
-                    || p->kind == SANS_CORE_SHELL_BICELLE || spheroid)
+                    || p->kind == SANS_CORE_SHELL_BICELLE || p->kind == SANS_STACKED_DISKS || spheroid)
                        ? 1 : 2;
         }
         a.quad_n = n;

@@ -34,7 +34,8 @@ KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelep
         "surface_fractal": 29, "two_power_law": 30, "guinier_porod": 31, "spinodal": 32, "porod": 33,
         "line": 34, "two_lorentzian": 35, "correlation_length": 36, "broad_peak": 37, "fractal": 38,
         "fractal_core_shell": 39, "polymer_excl_volume": 40, "elliptical_cylinder": 41,
-        "core_shell_bicelle": 42, "core_shell_parallelepiped": 43}
+        "core_shell_bicelle": 42, "core_shell_parallelepiped": 43, "core_shell_bicelle_elliptical": 44,
+        "stacked_disks": 45, "sc_paracrystal": 46, "bcc_paracrystal": 47, "fcc_paracrystal": 48}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 POLY_KIND = {"schulz": 0, "gaussian": 1}

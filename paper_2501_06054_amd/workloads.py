@@ -30,7 +30,9 @@ KINDS = ("sphere", "core_shell", "cylinder", "ellipsoid", "parallelepiped")
 EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle", "hollow_cylinder",
                "core_shell_cylinder", "core_shell_ellipsoid", "hollow_prism_thick", "fuzzy_sphere",
                "vesicle", "multilayer_vesicle", "linear_pearls", "fractal", "fractal_core_shell",
-               "elliptical_cylinder", "core_shell_bicelle", "core_shell_parallelepiped")
+               "elliptical_cylinder", "core_shell_bicelle", "core_shell_parallelepiped",
+               "core_shell_bicelle_elliptical", "stacked_disks", "sc_paracrystal", "bcc_paracrystal",
+               "fcc_paracrystal")
 #: shape-independent models: a cross-section in 1/cm, extra[0] = I(0)
 SHAPE_INDEPENDENT_KINDS = ("guinier", "ornstein_zernike", "dab", "gauss_coil", "poly_gauss_coil",
                            "teubner_strey", "power_law", "gaussian_peak", "lorentz_peak", "mass_fractal",
@@ -281,6 +283,17 @@ def oriented_elliptical_cylinder() -> dict:
                               orient_sigma=(10 * DEG, 10 * DEG, 10 * DEG), nx=256, ny=256))
 
 
+def oriented_fcc_paracrystal() -> dict:
+    """Spheres of radius 40 A on a face-centred cubic paracrystal (nearest
+    neighbours 220 A, distortion 0.06), cube axes tilted by 30/20/10 deg with
+    Gaussian spread 3 deg, volume fraction 0.2, 256x256, 1e9 neutrons."""
+    return dict(name="oriented_fcc_paracrystal", n=10**9, seed=23, exp_id=0,
+                params=params(kind="fcc_paracrystal", size=(40.0, 220.0, 0.0), sld=(1e-6, 0, 0),
+                              extra=(0.06, 0, 0, 0), phi=0.2, orient_kind="gaussian",
+                              orient_mean=(30 * DEG, 20 * DEG, 10 * DEG),
+                              orient_sigma=(3 * DEG, 3 * DEG, 3 * DEG), nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -303,6 +316,7 @@ WORKLOADS = {
     "multilayer_vesicle": multilayer_vesicle,
     "polymer_excl_volume": polymer_excl_volume,
     "oriented_elliptical_cylinder": oriented_elliptical_cylinder,
+    "oriented_fcc_paracrystal": oriented_fcc_paracrystal,
 }
 
 

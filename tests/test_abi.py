@@ -145,6 +145,10 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
      "SANS_E_INVALID_ARG"),
     (dict(kind="core_shell_parallelepiped", size=(10.0, 20.0, 30.0), extra=(1.0, -1.0, 1.0, 0)),
      "SANS_E_INVALID_ARG"),
+    (dict(kind="core_shell_bicelle_elliptical", size=(10.0, 20.0, 0.0), shell=1.0, extra=(1.0, 1e-6, 0.0, 0)),
+     "SANS_E_INVALID_ARG"),
+    (dict(kind="stacked_disks", size=(10.0, 20.0, 0.0), shell=1.0, extra=(2.5, 1.0, 0, 0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="fcc_paracrystal", size=(10.0, 50.0, 0.0), extra=(0.0, 0, 0, 0)), "SANS_E_INVALID_ARG"),
 ])
 def test_capped_body_params_rejected_without_gpu(S, over, code):
     from paper_2501_06054_amd import workloads as W
@@ -156,6 +160,6 @@ def test_capped_body_params_rejected_without_gpu(S, over, code):
 def test_unknown_kind_rejected_without_gpu(S):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=1.0))
-    sp.kind = 44
+    sp.kind = 49
     h = C.c_void_p()
     assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED

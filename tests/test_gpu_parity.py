@@ -269,6 +269,24 @@ PER_NEUTRON = {
                                          sld=(1e-6, 3e-6, 6.3e-6), extra=(4.0, 6.0, 3.0, 0),
                                          orient_kind="gaussian", orient_mean=(0.5, 1.0, 0.2),
                                          orient_sigma=(0.2, 0.2, 0.2)), 30011),
+    # elliptical bicelle, stacked disks, paracrystals
+    "bicelle_elliptical_gauss": (W.params(kind="core_shell_bicelle_elliptical", size=(25, 40, 0), shell=6.0,
+                                          sld=(1e-6, 4e-6, 6.3e-6), extra=(5.0, 2.5e-6, 1.8, 0),
+                                          orient_kind="gaussian", orient_mean=(1.2, 0.3, 0.5),
+                                          orient_sigma=(0.15, 0.15, 0.3)), 30011),
+    "stacked_disks_gauss": (W.params(kind="stacked_disks", size=(80, 25, 0), shell=8.0,
+                                     sld=(1e-6, 4e-6, 6.3e-6), extra=(8.0, 4.0, 0, 0), orient_kind="gaussian",
+                                     orient_mean=(1.4, 0.2, 0.0), orient_sigma=(0.1, 0.1, 0.0)), 30011),
+    "quad_stacked_disks": (W.params(kind="stacked_disks", mode="quad", size=(80, 25, 0), shell=8.0,
+                                    sld=(1e-6, 4e-6, 6.3e-6), extra=(5.0, 4.0, 0, 0), orient_kind="isotropic"),
+                           601),
+    "oriented_fcc_paracrystal": (W.workload("oriented_fcc_paracrystal")["params"], 50021),
+    "sc_paracrystal_fixed": (W.params(kind="sc_paracrystal", size=(30, 150, 0), extra=(0.08, 0, 0, 0),
+                                      orient_mean=(0.3, 0.7, 0.2)), 30011),
+    "bcc_paracrystal_iso": (W.params(kind="bcc_paracrystal", size=(30, 160, 0), extra=(0.1, 0, 0, 0),
+                                     orient_kind="isotropic", poly=0.1), 30011),
+    "quad_bcc_paracrystal": (W.params(kind="bcc_paracrystal", mode="quad", size=(30, 160, 0),
+                                      extra=(0.1, 0, 0, 0), orient_kind="isotropic", quad_n=40), 301),
 }
 
 
@@ -297,7 +315,7 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "oriented_hollow_prism_thick", "teubner_strey", "poly_gauss_coil", "dab", "mass_fractal",
              "star_polymer", "gaussian_peak", "multilayer_vesicle", "linear_pearls_poly", "spinodal",
              "fractal_poly", "polymer_excl_volume", "broad_peak", "oriented_elliptical_cylinder",
-             "bicelle_poly_iso", "cs_parallelepiped_gauss"]
+             "bicelle_poly_iso", "cs_parallelepiped_gauss", "stacked_disks_gauss", "oriented_fcc_paracrystal"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -331,7 +349,7 @@ def test_pq_avg_matches_oracle(S):
     for name in ("quad_parallelepiped", "quad_spheroid", "quad_coreshell", "quad_capped_cylinder",
                  "quad_hollow_prism", "quad_micelle_poly", "quad_hollow_cylinder",
                  "quad_core_shell_spheroid_poly", "quad_hollow_prism_thick", "quad_linear_pearls",
-                 "quad_elliptical_cylinder", "quad_bicelle"):
+                 "quad_elliptical_cylinder", "quad_bicelle", "quad_stacked_disks", "quad_bcc_paracrystal"):
         p, _ = PER_NEUTRON[name]
         m = S.Model(p)
         qs = np.concatenate([np.linspace(0.0, 0.06, 61), np.geomspace(1e-4, 0.3, 40)])
