@@ -29,7 +29,9 @@ KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelep
         "line": 34, "two_lorentzian": 35, "correlation_length": 36, "broad_peak": 37, "fractal": 38,
         "fractal_core_shell": 39, "polymer_excl_volume": 40, "elliptical_cylinder": 41,
         "core_shell_bicelle": 42, "core_shell_parallelepiped": 43, "core_shell_bicelle_elliptical": 44,
-        "stacked_disks": 45, "sc_paracrystal": 46, "bcc_paracrystal": 47, "fcc_paracrystal": 48}
+        "stacked_disks": 45, "sc_paracrystal": 46, "bcc_paracrystal": 47, "fcc_paracrystal": 48,
+        "mass_surface_fractal": 49, "gel_fit": 50}
+SQ_KIND = {"hard_sphere": 0, "sticky_hard_sphere": 1, "square_well": 2}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
 POLY_KIND = {"schulz": 0, "gaussian": 1}
@@ -49,8 +51,8 @@ class OrcParams(C.Structure):
         ("det_w", C.c_double), ("det_h", C.c_double), ("det_z", C.c_double),
         ("nx", C.c_int32), ("ny", C.c_int32),
         ("table_size", C.c_int32), ("quad_n", C.c_int32),
-        ("poly_kind", C.c_int32), ("pad_", C.c_int32),
-        ("extra", C.c_double * 4),
+        ("poly_kind", C.c_int32), ("sq_kind", C.c_int32),
+        ("extra", C.c_double * 4), ("sq_extra", C.c_double * 2),
     ]
 
 
@@ -89,6 +91,12 @@ def lib():
             getattr(L, f).restype = d
         L.orc_py_sq.argtypes = [d, d, d]
         L.orc_py_sq.restype = d
+        L.orc_sticky_lambda.argtypes = [d, d]
+        L.orc_sticky_lambda.restype = d
+        L.orc_sticky_sq.argtypes = [d, d, d, d]
+        L.orc_sticky_sq.restype = d
+        L.orc_square_well_sq.argtypes = [d, d, d, d, d]
+        L.orc_square_well_sq.restype = d
         L.orc_py_series.argtypes = [d, i32, P(d)]
         L.orc_table_normal.argtypes = [i32, P(d)]
         L.orc_table_truncnorm.argtypes = [i32, d, P(d)]
@@ -148,6 +156,9 @@ def to_params(p: dict) -> OrcParams:
     o.poly_kind = POLY_KIND[p.get("poly_kind", "schulz")]
     for k, v in enumerate(p.get("extra", (0.0, 0.0, 0.0, 0.0))):
         o.extra[k] = float(v)
+    o.sq_kind = SQ_KIND[p.get("sq_kind", "hard_sphere")]
+    for k, v in enumerate(p.get("sq_extra", (0.0, 0.0))):
+        o.sq_extra[k] = float(v)
     return o
 
 
@@ -231,6 +242,19 @@ def sinc(x: float) -> float:
 
 def py_sq(q: float, radius: float, phi: float) -> float:
     return lib().orc_py_sq(q, radius, phi)
+
+
+def sticky_lambda(eta: float, tau: float) -> float:
+    """Baxter's lambda of adhesive hard spheres (NaN inside the two-phase region)."""
+    return lib().orc_sticky_lambda(eta, tau)
+
+
+def sticky_sq(q: float, radius: float, eta: float, tau: float) -> float:
+    return lib().orc_sticky_sq(q, radius, eta, tau)
+
+
+def square_well_sq(q: float, radius: float, eta: float, depth: float, width: float) -> float:
+    return lib().orc_square_well_sq(q, radius, eta, depth, width)
 
 
 def py_series(phi: float, nterms: int) -> np.ndarray:

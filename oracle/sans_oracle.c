@@ -68,7 +68,9 @@ typedef struct {
                               parallelepiped, 44 elliptical core-shell
                               bicelle, 45 stacked disks, 46 simple cubic,
                               47 body-centred, 48 face-centred cubic
-                              paracrystals of spheres                       */
+                              paracrystals of spheres; shape-independent:
+                              49 mass-surface fractal, 50 gel (fractal
+                              network plus frozen inhomogeneities)          */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -98,10 +100,14 @@ typedef struct {
     int32_t quad_n;        /* Gauss-Legendre order of the exact average      */
     int32_t poly_kind;     /* size distribution: 0 Schulz, 1 Gaussian kept
                               only where the size is positive                */
-    int32_t pad_;
+    int32_t sq_kind;       /* structure factor when sq_phi > 0: 0 hard
+                              spheres (Percus-Yevick), 1 adhesive hard spheres
+                              (Baxter), 2 square-well (mean spherical)     */
     double extra[4];       /* micelle: aggregation number N, core-block and
                               corona-chain volumes (A^3), penetration d;
                               core-shell cylinder: extra[0] = end-face shell */
+    double sq_extra[2];    /* adhesive spheres: stickiness tau; square well:
+                              depth (kT) and width (in diameters)           */
 } orc_params;
 
 /* Surrogate mode (mode 2): a network replaces the exact average; set with
@@ -389,6 +395,87 @@ double orc_py_sq(double q, double radius, double phi)
     return 1.0 / (1.0 + 24.0 * phi * gx);
 }
 
+void orc_gauss_legendre(int32_t n, double* x, double* w);
+
+/* Adhesive hard spheres in the Percus-Yevick closure (Baxter's model:
+ * diameter sigma, volume fraction eta, stickiness tau).  lambda is the
+ * smaller root of (eta/12) l^2 - (tau + eta/(1 - eta)) l + (1 + eta/2)/(1 - eta)^2;
+ * NaN when the roots are complex (inside the model's two-phase region). */
+double orc_sticky_lambda(double eta, double tau)
+{
+    double a = eta / 12.0, b = -(tau + eta / (1.0 - eta));
+    double c = (1.0 + 0.5 * eta) / ((1.0 - eta) * (1.0 - eta));
+    double disc = b * b - 4.0 * a * c;
+    if (disc < 0.0) return NAN;
+    if (a == 0.0) return c / -b;
+    return (-b - sqrt(disc)) / (2.0 * a);
+}
+
+/* S(q) = 1 / |Qhat(k)|^2 with Baxter's factor function: in units of sigma,
+ * Q(x) = (a/2)(x^2 - 1) + b (x - 1) + lambda/12 on 0 <= x <= 1, with
+ * mu = lambda eta (1 - eta), a = (1 + 2 eta - mu)/(1 - eta)^2,
+ * b = (mu - 3 eta)/(2 (1 - eta)^2), and Qhat(k) = 1 - 12 eta int_0^1 Q(x)
+ * exp(i k x) dx, k = q sigma.  The integral by composite Gauss-Legendre
+ * (32 nodes on each of 1 + k/4 panels: Q is a quadratic, the panels follow
+ * the oscillation of exp(i k x)). */
+double orc_sticky_sq(double q, double radius, double eta, double tau)
+{
+    if (eta <= 0.0) return 1.0;
+    double lam = orc_sticky_lambda(eta, tau);
+    double mu = lam * eta * (1.0 - eta);
+    double om2 = (1.0 - eta) * (1.0 - eta);
+    double a = (1.0 + 2.0 * eta - mu) / om2, b = (mu - 3.0 * eta) / (2.0 * om2);
+    double k = 2.0 * q * radius;
+    double gx[32], gw[32];
+    orc_gauss_legendre(32, gx, gw);
+    int npan = 1 + (int)(k / 4.0);
+    double h = 1.0 / npan, re = 0.0, im = 0.0;
+    for (int j = 0; j < npan; ++j) {
+        for (int i = 0; i < 32; ++i) {
+            double x = h * (j + 0.5 * (gx[i] + 1.0)), w = 0.5 * h * gw[i];
+            double qx = 0.5 * a * (x * x - 1.0) + b * (x - 1.0) + lam / 12.0;
+            re += w * qx * cos(k * x);
+            im += w * qx * sin(k * x);
+        }
+    }
+    double A = 1.0 - 12.0 * eta * re, B = -12.0 * eta * im;
+    return 1.0 / (A * A + B * B);
+}
+
+/* Square-well fluid in the mean spherical approximation (Sharma and Sharma):
+ * the hard-sphere (Percus-Yevick) direct correlation plus, between sigma and
+ * width * sigma, c(r) = depth (the well's depth in kT, attractive when
+ * positive), so 1/S = 1/S_PY - rho c_well(q) with
+ * rho c_well(q) = 24 eta depth int_1^width x^2 sin(k x)/(k x) dx, k = q sigma
+ * (composite Gauss-Legendre, 32 nodes on each of 1 + k (width - 1)/4 panels). */
+double orc_square_well_sq(double q, double radius, double eta, double depth, double width)
+{
+    if (eta <= 0.0) return 1.0;
+    double k = 2.0 * q * radius;
+    double gx[32], gw[32];
+    orc_gauss_legendre(32, gx, gw);
+    int npan = 1 + (int)(k * (width - 1.0) / 4.0);
+    double h = (width - 1.0) / npan, integral = 0.0;
+    for (int j = 0; j < npan; ++j) {
+        for (int i = 0; i < 32; ++i) {
+            double x = 1.0 + h * (j + 0.5 * (gx[i] + 1.0));
+            double kx = k * x;
+            double sinc = kx < 1e-8 ? 1.0 : sin(kx) / kx;
+            integral += 0.5 * h * gw[i] * x * x * sinc;
+        }
+    }
+    return 1.0 / (1.0 / orc_py_sq(q, radius, eta) - 24.0 * eta * depth * integral);
+}
+
+/* The structure factor selected by sq_kind (1 when sq_phi = 0). */
+static double struct_factor(const orc_params* p, double q)
+{
+    if (!(p->sq_phi > 0.0)) return 1.0;
+    if (p->sq_kind == 1) return orc_sticky_sq(q, p->sq_radius, p->sq_phi, p->sq_extra[0]);
+    if (p->sq_kind == 2) return orc_square_well_sq(q, p->sq_radius, p->sq_phi, p->sq_extra[0], p->sq_extra[1]);
+    return orc_py_sq(q, p->sq_radius, p->sq_phi);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Particle amplitudes F (the Fourier transform of the excess scattering
  * length density, Eq. (1)), in Angstrom: F^2 = (drho V)^2 P.  The particle
@@ -638,7 +725,7 @@ static double micelle_f2(const double s[3], const double sld[3], const double ex
  * in 1/cm, scale = its value at q = 0 (extra[0]); the length is size[0]. */
 static int shape_independent(int kind)
 {
-    return (kind >= 13 && kind <= 24) || (kind >= 29 && kind <= 37) || kind == 40;
+    return (kind >= 13 && kind <= 24) || (kind >= 29 && kind <= 37) || kind == 40 || kind == 49 || kind == 50;
 }
 
 /* Fractal aggregates of spherical blocks (radius R0): Teixeira's structure
@@ -774,6 +861,25 @@ static double shape_independent_iq(const orc_params* p, const double s[3], doubl
         }
         double g1 = tgamma(s1) * orc_gamma_p(s1, u), g2 = tgamma(s2) * orc_gamma_p(s2, u);
         return scale * (g1 / pow(u, s1) - g2 / pow(u, s2)) / nu;
+    }
+    case 49: { /* mass-surface fractal (Hurd, Schaefer and Martin): clusters of
+                  mass dimension Dm = extra[1] and radius of gyration
+                  Rc = size[0] built of primary particles with fractal
+                  surfaces of dimension Ds = extra[2] and radius of gyration
+                  Rp = size[1]; two generalised Lorentzians, each with the
+                  Guinier radius of its level:
+                  (1 + (q Rc)^2/(3 pm))^-pm (1 + (q Rp)^2/(3 ps))^-ps,
+                  pm = Dm/2, ps = (6 - Ds - Dm)/2 (so q^-(6-Ds) at large q) */
+        double pm = 0.5 * p->extra[1], ps = 0.5 * (6.0 - p->extra[2] - p->extra[1]);
+        double qp = q * s[1];
+        return scale * pow(1.0 + x / (3.0 * pm), -pm) * pow(1.0 + qp * qp / (3.0 * ps), -ps);
+    }
+    case 50: { /* gel: a fractal network of mesh size xi = size[0] and dimension
+                  D = extra[2], extra[0] (1 + (D + 1)/3 (q xi)^2)^(-D/2), plus
+                  frozen inhomogeneities of radius of gyration Rg = size[1] as a
+                  Guinier term extra[1] exp(-(q Rg)^2 / 3) */
+        double d = p->extra[2], qg = q * s[1];
+        return scale * pow(1.0 + (d + 1.0) / 3.0 * x, -0.5 * d) + p->extra[1] * exp(-qg * qg / 3.0);
     }
     }
     return 0.0;
@@ -1397,7 +1503,7 @@ static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_
         f2 = surrogate_f2(p, q, &in_domain);
         if (!in_domain) f2 = pq_avg_nodes(p, q, qv, cx->gx, cx->gw);
     }
-    double sq = (p->sq_phi > 0.0) ? orc_py_sq(q, p->sq_radius, p->sq_phi) : 1.0;
+    double sq = struct_factor(p, q);
     double w = len * 1e10 * cx->prefactor * f2 * sq;
     for (int a = 0; a < 3; ++a) {
         ev.qv[a] = qv[a];

@@ -38,10 +38,14 @@ SHAPE_INDEPENDENT_KINDS = ("guinier", "ornstein_zernike", "dab", "gauss_coil", "
                            "teubner_strey", "power_law", "gaussian_peak", "lorentz_peak", "mass_fractal",
                            "star_polymer", "gauss_lorentz_gel", "surface_fractal", "two_power_law",
                            "guinier_porod", "spinodal", "porod", "line", "two_lorentzian", "correlation_length",
-                           "broad_peak", "polymer_excl_volume")
+                           "broad_peak", "polymer_excl_volume", "mass_surface_fractal", "gel_fit")
 ORIENT_KINDS = ("fixed", "gaussian", "isotropic", "uniform_angles")
 MODES = ("mc", "quad", "surrogate")
 POLY_KINDS = ("schulz", "gaussian")
+#: structure factors (when sq_phi > 0): Percus-Yevick hard spheres, Baxter's
+#: adhesive hard spheres (sq_extra[0] = stickiness), square-well fluid in the
+#: mean spherical approximation (sq_extra = depth in kT, width in diameters)
+SQ_KINDS = ("hard_sphere", "sticky_hard_sphere", "square_well")
 
 DEG = math.pi / 180.0
 
@@ -60,7 +64,7 @@ INSTRUMENT = dict(
 SAMPLE_DEFAULTS = dict(
     kind="sphere", mode="mc",
     size=(50.0, 0.0, 0.0), shell=0.0, sld=(1e-6, 0.0, 0.0),
-    phi=0.01, sq_phi=0.0, sq_radius=0.0,
+    phi=0.01, sq_phi=0.0, sq_radius=0.0, sq_kind="hard_sphere", sq_extra=(0.0, 0.0),
     poly=0.0, poly_mask=1, poly_kind="schulz",
     orient_kind="fixed", orient_mean=(0.0, 0.0, 0.0), orient_sigma=(0.0, 0.0, 0.0),
     table_size=4096, quad_n=76,
@@ -76,7 +80,7 @@ def params(**over) -> dict:
         if k not in p:
             raise KeyError(f"unknown parameter {k!r}")
         p[k] = v
-    for k in ("size", "sld", "orient_mean", "orient_sigma", "extra"):
+    for k in ("size", "sld", "orient_mean", "orient_sigma", "extra", "sq_extra"):
         p[k] = tuple(float(x) for x in p[k])
     return p
 

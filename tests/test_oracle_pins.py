@@ -1427,3 +1427,100 @@ def test_paracrystal_factor_and_reflections(orc, kind):
         q = float(np.linalg.norm(qv))
         zr = orc.form_f2(p, q, tuple(qv), 1.0, (0, 0, 0)) / orc.amplitude(sph, q, tuple(qv)) ** 2
         assert zr < 1.0
+
+
+# ---------------------------------------------------------------- mass-surface fractal, gel
+
+def _iq(orc, p, q):
+    return orc.form_f2(p, q, (0.0, 0.0, q))
+
+
+@pytest.mark.parametrize("dm,ds", [(1.8, 2.3), (2.5, 2.1), (1.2, 3.0)])
+def test_mass_surface_fractal_limits(orc, dm, ds):
+    """I(0) is the scale; the Guinier radius^2 is the sum of the two levels'
+    (each factor has its own Guinier radius); the slope is -Dm between the
+    two levels and -(6 - Ds) beyond the primary particles."""
+    rc, rp = 120.0, 15.0
+    p = W.params(kind="mass_surface_fractal", size=(rc, rp, 0.0), extra=(4.0, dm, ds, 0.0))
+    assert _iq(orc, p, 0.0) == pytest.approx(4.0, rel=1e-15)
+    q = 1e-5
+    rg2 = 3.0 * (math.log(4.0) - math.log(_iq(orc, p, q))) / q ** 2
+    assert rg2 == pytest.approx(rc ** 2 + rp ** 2, rel=1e-6)
+    slope = lambda pp, q: math.log(_iq(orc, pp, 1.001 * q) / _iq(orc, pp, q)) / math.log(1.001)
+    assert slope(p, 1e3 / rp) == pytest.approx(-(6.0 - ds), abs=2e-4)
+    wide = W.params(kind="mass_surface_fractal", size=(1e6, 1e-3, 0.0), extra=(4.0, dm, ds, 0.0))
+    assert slope(wide, 1e-1) == pytest.approx(-dm, abs=1e-4)
+
+
+@pytest.mark.parametrize("q", [0.0, 0.003, 0.02, 0.07])
+def test_gel_fit_reduces_to_ornstein_zernike_plus_guinier(orc, q):
+    """At network dimension 2 the network term is the Ornstein-Zernike
+    Lorentzian of the mesh size, the second term the Guinier law."""
+    xi, rg = 40.0, 150.0
+    gel = W.params(kind="gel_fit", size=(xi, rg, 0.0), extra=(3.0, 0.5, 2.0, 0.0))
+    oz = W.params(kind="ornstein_zernike", size=(xi, 0.0, 0.0), extra=(3.0, 0.0, 0.0, 0.0))
+    gu = W.params(kind="guinier", size=(rg, 0.0, 0.0), extra=(0.5, 0.0, 0.0, 0.0))
+    assert _iq(orc, gel, q) == pytest.approx(_iq(orc, oz, q) + _iq(orc, gu, q), rel=1e-14)
+
+
+@pytest.mark.parametrize("d", [1.0, 1.7, 2.6])
+def test_gel_fit_network_slope_and_forward_value(orc, d):
+    xi = 30.0
+    p = W.params(kind="gel_fit", size=(xi, 100.0, 0.0), extra=(2.0, 0.0, d, 0.0))
+    assert _iq(orc, p, 0.0) == pytest.approx(2.0, rel=1e-15)
+    q = 1e3 / xi
+    assert math.log(_iq(orc, p, 1.001 * q) / _iq(orc, p, q)) / math.log(1.001) == pytest.approx(-d, abs=1e-5)
+    p2 = W.params(kind="gel_fit", size=(xi, 100.0, 0.0), extra=(2.0, 0.7, d, 0.0))
+    assert _iq(orc, p2, 0.0) == pytest.approx(2.7, rel=1e-15)
+
+
+# ---------------------------------------------------------------- adhesive and square-well S(q)
+
+@pytest.mark.parametrize("eta", [0.05, 0.2, 0.35])
+def test_sticky_spheres_without_adhesion_are_percus_yevick(orc, eta):
+    """tau -> infinity removes the adhesion (lambda -> 0): Baxter's factor
+    function is then the hard-sphere one, whose S(q) the pinned Percus-Yevick
+    closed form gives."""
+    for q in (0.0, 0.002, 0.02, 0.05, 0.12, 1.0, 4.0):
+        assert orc.sticky_sq(q, 40.0, eta, 1e12) == pytest.approx(orc.py_sq(q, 40.0, eta), rel=1e-9)
+
+
+@pytest.mark.parametrize("eta,tau", [(0.05, 0.15), (0.1, 0.2), (0.3, 0.5), (0.2, 1.0)])
+def test_sticky_spheres_compressibility(orc, eta, tau):
+    """S(0) = (1 - eta)^4 / (1 + 2 eta - mu)^2, mu = lambda eta (1 - eta)
+    (the compressibility of Baxter's adhesive spheres); adhesion raises it
+    above the hard-sphere value, more so at smaller tau; S -> 1 at large q."""
+    lam = orc.sticky_lambda(eta, tau)
+    mu = lam * eta * (1.0 - eta)
+    assert orc.sticky_sq(0.0, 40.0, eta, tau) == pytest.approx((1 - eta) ** 4 / (1 + 2 * eta - mu) ** 2, rel=1e-12)
+    assert orc.sticky_sq(0.0, 40.0, eta, tau) > orc.sticky_sq(0.0, 40.0, eta, 2 * tau) > orc.py_sq(0.0, 40.0, eta)
+    assert orc.sticky_sq(3.0, 40.0, eta, tau) == pytest.approx(1.0, abs=2e-2)
+
+
+def test_sticky_spheres_critical_point(orc):
+    """Baxter's critical point, eta_c = (3 sqrt 2 - 4)/2, tau_c = (2 - sqrt 2)/6:
+    the two roots for lambda merge there, none exists below tau_c, and the
+    compressibility diverges (mu = 1 + 2 eta)."""
+    ec = (3 * math.sqrt(2) - 4) / 2
+    tc = (2 - math.sqrt(2)) / 6
+    assert math.isnan(orc.sticky_lambda(ec, tc * (1 - 1e-6)))
+    lam = orc.sticky_lambda(ec, tc * (1 + 1e-12))
+    assert lam * ec * (1 - ec) == pytest.approx(1 + 2 * ec, rel=1e-5)
+    assert orc.sticky_sq(0.0, 40.0, ec, tc * (1 + 1e-12)) > 1e8
+
+
+@pytest.mark.parametrize("eta,depth,width", [(0.1, 1.0, 1.5), (0.2, 0.5, 1.2), (0.3, -0.8, 1.8)])
+def test_square_well_closed_form_and_limits(orc, eta, depth, width):
+    """The well adds the transform of a constant c(r) = depth on [sigma,
+    width sigma], 8 eta depth (width^3 Phi(width k) - Phi(k)) with the
+    sphere's Phi(y) = 3 (sin y - y cos y)/y^3; no well gives Percus-Yevick."""
+    R = 30.0
+    phi_ = lambda y: 1.0 if y == 0 else 3 * (math.sin(y) - y * math.cos(y)) / y ** 3
+    for q in (0.0, 0.004, 0.03, 0.09, 1.5):
+        k = 2 * q * R
+        inv = 1 / orc.py_sq(q, R, eta) - 8 * eta * depth * (width ** 3 * phi_(width * k) - phi_(k))
+        assert orc.square_well_sq(q, R, eta, depth, width) == pytest.approx(1 / inv, rel=1e-11)
+        assert orc.square_well_sq(q, R, eta, 0.0, width) == pytest.approx(orc.py_sq(q, R, eta), rel=1e-15)
+        assert orc.square_well_sq(q, R, eta, depth, 1.0) == pytest.approx(orc.py_sq(q, R, eta), rel=1e-15)
+    s0 = 1 / ((1 + 2 * eta) ** 2 / (1 - eta) ** 4 - 8 * eta * depth * (width ** 3 - 1))
+    assert orc.square_well_sq(0.0, R, eta, depth, width) == pytest.approx(s0, rel=1e-12)
