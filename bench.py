@@ -85,6 +85,8 @@ STEP = {
     "pev_I":         ((2,   0,  0, 500, 0, 3), 0),  # excluded-volume chain: two FP64 incomplete gammas (~30 series
                                                     # or continued-fraction steps of 4 ops each, exp, log)
     "py_sq":         ((15,  0,  0,  0, 1, 0), 25),  # A10: series in x^2, 1/(1 + 24 phi G/x)
+    "sticky_sq":     ((27,  0,  0,  0, 1, 0), 50),  # adhesive spheres: two series in k^2, A^2 + B^2, reciprocal
+    "msf_I":         ((8,   0,  0,  3, 3, 0), 10),  # mass-surface fractal: two log2, one exp2
     "weight":        ((3,   0,  0,  2, 0, 0), 3),   # A11
     "detector":      ((0,   5,  0, 23, 0, 1), 0),   # A12: plane crossing (quotient), pixel
     "tally":         ((0,   2,  0,  0, 0, 0), 0),   # A13: address; the add itself is a memory op
@@ -127,6 +129,9 @@ PATHS = {
                                     + ["qvec"] + ["orient_angle"] * 3 + ["project_abc", "ellcyl_F"],
     "oriented_fcc_paracrystal": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
                                 + ["qvec"] + ["orient_angle"] * 3 + ["project_abc", "sphere_F", "paracrystal_Z"],
+    "sticky_coreshell": COMMON + ["philox_block"] * 3 + ["uniform"] * 9
+                        + ["size_draw", "core_shell_F", "sticky_sq"],
+    "mass_surface_fractal": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["msf_I"],
 }
 # Exact-average paths, per quadrature node (76 x 76 = 5776 nodes per neutron),
 # all FP32:

@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define SANS_ABI_VERSION 3u
+#define SANS_ABI_VERSION 4u
 
 /* Status codes. */
 #define SANS_OK 0
@@ -172,8 +172,37 @@ typedef enum {
                                     distortion factor extra[0] in (0, 1); the
                                     cubic axes along A, B, C                   */
     SANS_BCC_PARACRYSTAL = 47,   /* the same, body-centred cubic               */
-    SANS_FCC_PARACRYSTAL = 48    /* the same, face-centred cubic               */
+    SANS_FCC_PARACRYSTAL = 48,   /* the same, face-centred cubic               */
+    /* The last shape-independent models (cross-sections in 1/cm, as above). */
+    SANS_MASS_SURFACE_FRACTAL = 49, /* clusters (mass dimension Dm = extra[1],
+                                    radius of gyration L) of primary particles
+                                    with surface dimension Ds = extra[2] and
+                                    radius of gyration size[1] >= 0:
+                                    (1 + (qL)^2/(3 pm))^-pm (1 + (q size[1])^2/(3 ps))^-ps,
+                                    pm = Dm/2 > 0, ps = (6 - Ds - Dm)/2 > 0    */
+    SANS_GEL_FIT = 50            /* network of mesh size L and dimension D =
+                                    extra[2] in (0, 6]:
+                                    extra[0] (1 + (D + 1)/3 (qL)^2)^(-D/2),
+                                    plus frozen inhomogeneities extra[1]
+                                    exp(-(q size[1])^2/3), size[1] >= 0       */
 } sans_kind;
+
+/* Structure factor S(q) of the particles (when sq_phi > 0): volume fraction
+ * sq_phi, particle radius sq_radius (diameter sigma = 2 sq_radius). */
+typedef enum {
+    SANS_SQ_HARD_SPHERE = 0,     /* Percus-Yevick hard spheres                  */
+    SANS_SQ_STICKY_HARD_SPHERE = 1, /* Baxter's adhesive hard spheres (Percus-
+                                    Yevick closure), stickiness tau =
+                                    sq_extra[0] > 0; SANS_E_DOMAIN where no
+                                    solution exists (tau below the two-phase
+                                    boundary)                                  */
+    SANS_SQ_SQUARE_WELL = 2      /* square-well fluid, mean spherical
+                                    approximation: well depth sq_extra[0] (kT,
+                                    attractive when > 0) from sigma out to
+                                    sq_extra[1] sigma (width in [1, 4]);
+                                    SANS_E_DOMAIN where 1/S(q) <= 0 inside the
+                                    instrument's q range                       */
+} sans_sq_kind;
 
 /* How the particle size and orientation enter the weight. */
 typedef enum {
@@ -241,7 +270,7 @@ typedef enum {
  *   w = l[A] * dOmega * (phi / <V>) * F^2 * S(q),
  * dOmega = 2 pi (1 - cos cone_alpha), F the particle amplitude in Angstrom
  * (F^2 = (drho V)^2 P), <V> the number-averaged particle volume, S the
- * Percus-Yevick hard-sphere structure factor of radius sq_radius and volume
+ * structure factor sq_kind (sans_sq_kind) of radius sq_radius and volume
  * fraction sq_phi (S = 1 when sq_phi = 0; fixed radius, decoupled from the
  * drawn size).  Misses of the sample or the detector are not tallied. */
 typedef struct {
@@ -274,9 +303,10 @@ typedef struct {
                                 mode                                           */
     int32_t tally;           /* sans_tally                                     */
     int32_t poly_kind;       /* sans_poly                                      */
-    int32_t reserved;        /* 0                                              */
+    int32_t sq_kind;         /* sans_sq_kind                                   */
     double extra[4];         /* model parameters beyond size and shell (see
                                 sans_kind; unused entries 0)                   */
+    double sq_extra[2];      /* structure-factor parameters (sans_sq_kind)     */
 } sans_params;
 
 typedef struct sans_model_s* sans_model_t;

@@ -80,10 +80,16 @@ struct TraceArgs {
     float contrast;               // drho = sld[0] - sld[2]
     float cs_core, cs_shell;      // core-shell: sld0 - sld1, sld1 - sld2
     int32_t poly_on, poly_mask, orient_kind, third_block;
-    int32_t sq_on;
+    int32_t sq_on, sq_kind;       // sq_kind: 0 hard spheres, 1 adhesive, 2 square well
     float sq_2r, sq_24phi;
     float py_alpha, py_beta, py_gamma;
     float py_c[kPySeriesTerms];
+    // adhesive hard spheres: series of A(k) and B(k)/k in k^2, 12 eta and the
+    // factor function's coefficients h, b, c0 (h x^2 + b x + c0)
+    float sh_ca[kPySeriesTerms], sh_cb[kPySeriesTerms];
+    float sh_e, sh_h, sh_b, sh_c0;
+    // square well: 8 eta depth, width, width^3
+    float sw_8de, sw_w, sw_w3;
     // tables (device global memory, FP64 knots; kernels stage them in LDS)
     int32_t M;                    // knots per table
     const double* tab_size;       // Schulz quantiles or nullptr
@@ -381,12 +387,11 @@ __device__ __forceinline__ float sinc_f(float x)
     return s * rcpf(x);
 }
 
-// Percus-Yevick hard-sphere S(q): x = 2 q R, S = 1/(1 + 24 phi G(x)/x).
-// Below x = 2.5 G(x)/x comes from its power series (coefficients computed on
-// the host); above, from the closed form.
-__device__ __forceinline__ float py_sq(const TraceArgs& a, float q)
+// Percus-Yevick hard spheres: 1/S(q) = 1 + 24 phi G(x)/x, x = 2 q R.  Below
+// x = 2.5 G(x)/x comes from its power series (coefficients computed on the
+// host); above, from the closed form.
+__device__ __forceinline__ float py_inv_sq(const TraceArgs& a, float x)
 {
-    const float x = q * a.sq_2r;
     float gx;
     if (x < 2.5f) {
         const float x2 = x * x;
@@ -406,7 +411,54 @@ __device__ __forceinline__ float py_sq(const TraceArgs& a, float q)
                        * ix2 * ix2 * ix;
         gx = (a.py_alpha * ta + a.py_beta * tb + a.py_gamma * tg) * ix;
     }
-    return rcpf(__builtin_fmaf(a.sq_24phi, gx, 1.0f));
+    return __builtin_fmaf(a.sq_24phi, gx, 1.0f);
+}
+
+// Adhesive hard spheres (Baxter): S = 1/(A^2 + B^2) with A, B the real and
+// imaginary parts of 1 - 12 eta int_0^1 Q(x) exp(i k x) dx, k = q sigma, Q
+// the quadratic factor function; power series in k^2 below k = 2.5, above
+// the closed forms of int x^n cos(kx) and int x^n sin(kx) (n = 0, 1, 2).
+__device__ __forceinline__ float sticky_sq(const TraceArgs& a, float k)
+{
+    float A, B;
+    if (k < 2.5f) {
+        const float k2 = k * k;
+        float ra = a.sh_ca[kPySeriesTerms - 1], rb = a.sh_cb[kPySeriesTerms - 1];
+#pragma unroll
+        for (int m = kPySeriesTerms - 2; m >= 0; --m) {
+            ra = __builtin_fmaf(ra, k2, a.sh_ca[m]);
+            rb = __builtin_fmaf(rb, k2, a.sh_cb[m]);
+        }
+        A = ra;
+        B = rb * k;
+    } else {
+        float s, c;
+        sincos_f(k, s, c);
+        const float ik = rcpf(k);
+        const float ks = k * s, kc = k * c;
+        const float c0 = s * ik;
+        const float c1 = (ks + c - 1.0f) * ik * ik;
+        const float c2 = __builtin_fmaf(k, ks, 2.0f * (kc - s)) * ik * ik * ik;
+        const float s0 = (1.0f - c) * ik;
+        const float s1 = (s - kc) * ik * ik;
+        const float s2 = (__builtin_fmaf(-k, kc, 2.0f * (ks + c)) - 2.0f) * ik * ik * ik;
+        A = __builtin_fmaf(-a.sh_e, __builtin_fmaf(a.sh_h, c2, __builtin_fmaf(a.sh_b, c1, a.sh_c0 * c0)), 1.0f);
+        B = a.sh_e * __builtin_fmaf(a.sh_h, s2, __builtin_fmaf(a.sh_b, s1, a.sh_c0 * s0));
+    }
+    return rcpf(__builtin_fmaf(A, A, B * B));
+}
+
+// The structure factor of the model (the kind is the same for every lane):
+// hard spheres; adhesive spheres; the square well, whose mean-spherical
+// direct correlation adds 8 eta depth (w^3 Phi(w x) - Phi(x)) to the
+// hard-sphere one (Phi the sphere's 3 j1(y)/y).
+__device__ __forceinline__ float struct_factor(const TraceArgs& a, float q)
+{
+    const float x = q * a.sq_2r;
+    if (a.sq_kind == 1) return sticky_sq(a, x);
+    float inv = py_inv_sq(a, x);
+    if (a.sq_kind == 2) inv = __builtin_fmaf(-a.sw_8de, __builtin_fmaf(a.sw_w3, sph3j_f(a.sw_w * x), -sph3j_f(x)), inv);
+    return rcpf(inv);
 }
 
 // Linear interpolation in an FP64 inverse-CDF table (knots at (k + 1/2)/M).
@@ -498,7 +550,8 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kLine = 34, kTwoLorentzian = 35, kCorrelationLength = 36, kBroadPeak = 37, kFractal = 38,
               kFractalCoreShell = 39, kPolymerExclVolume = 40, kEllipticalCylinder = 41,
               kCoreShellBicelle = 42, kCoreShellParallelepiped = 43, kCoreShellBicelleElliptical = 44,
-              kStackedDisks = 45, kScParacrystal = 46, kBccParacrystal = 47, kFccParacrystal = 48 };
+              kStackedDisks = 45, kScParacrystal = 46, kBccParacrystal = 47, kFccParacrystal = 48,
+              kMassSurfaceFractal = 49, kGelFit = 50 };
 
 // F^2 multiplied by an orientation-dependent interference factor (stacked
 // disks, paracrystals).
@@ -509,7 +562,8 @@ constexpr bool kLattice = KIND >= kStackedDisks && KIND <= kFccParacrystal;
 template <int KIND>
 constexpr bool kShapeIndependent = (KIND >= kGuinier && KIND <= kGaussLorentzGel)
                                    || (KIND >= kSurfaceFractal && KIND <= kBroadPeak)
-                                   || KIND == kPolymerExclVolume;
+                                   || KIND == kPolymerExclVolume || KIND == kMassSurfaceFractal
+                                   || KIND == kGelFit;
 
 // Isotropic sphere-based particles (fuzzy sphere, vesicles, pearl strings,
 // fractal aggregates of spheres).
@@ -762,6 +816,18 @@ __device__ __forceinline__ float shape_iq(const TraceArgs& a, double len, double
         const double v = (double)a.si_scale * exp2(-a.si_a * log2(q))
                        + a.si_b / (1.0 + exp2(a.si_c * log2(dq * a.si_d)));
         return (float)v;
+    } else if constexpr (KIND == kMassSurfaceFractal) {
+        // (1 + x/(3 pm))^-pm (1 + (q Rp)^2/(3 ps))^-ps: si_a = 1/(3 pm),
+        // si_b = pm, si_c = Rp^2/(3 ps), si_d = ps
+        const float xp = (float)(q * q * a.si_c);
+        const float l2 = __builtin_fmaf((float)a.si_b, log2f(__builtin_fmaf(x, (float)a.si_a, 1.0f)),
+                                        (float)a.si_d * log2f(1.0f + xp));
+        return a.si_scale * exp2f(-l2);
+    } else if constexpr (KIND == kGelFit) {
+        // extra[0] (1 + (D + 1)/3 x)^(-D/2) + extra[1] exp(-(q Rg)^2/3):
+        // si_a = (D + 1)/3, si_b = D/2, si_c = extra[1], si_d = Rg^2/3
+        const float net = exp2f(-(float)a.si_b * log2f(__builtin_fmaf(x, (float)a.si_a, 1.0f)));
+        return __builtin_fmaf(a.si_scale, net, (float)a.si_c * __expf(-(float)(q * q * a.si_d)));
     } else {
         // polymer with excluded volume: (g(s1, U)/U^s1 - g(s2, U)/U^s2)/nu with
         // the lower incomplete gamma g, s1 = 1/(2 nu), s2 = 1/nu (FP64); a series
@@ -1437,7 +1503,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
         f2 = 1.0f;
     }
     float w = (float)(len * a.wscale) * f2;
-    if (a.sq_on) w *= py_sq(a, q);
+    if (a.sq_on) w *= struct_factor(a, q);
     if (on_det) {
         ev.pixel = (int32_t)fyp * a.nx + (int32_t)fxp;
         ev.w = w;

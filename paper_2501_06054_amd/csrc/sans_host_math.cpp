@@ -132,6 +132,39 @@ void py_series(double phi, int nterms, double* c, double* abg)
     }
 }
 
+// Adhesive hard spheres in the Percus-Yevick closure (Baxter): the adhesion
+// parameter lambda is the smaller root of
+// (eta/12) l^2 - (tau + eta/(1 - eta)) l + (1 + eta/2)/(1 - eta)^2 = 0; with
+// mu = lambda eta (1 - eta) the factor function is
+// Q(x) = a/2 (x^2 - 1) + b (x - 1) + lambda/12, a = (1 + 2 eta - mu)/(1 - eta)^2,
+// b = (mu - 3 eta)/(2 (1 - eta)^2).  Its moments m_n = int_0^1 Q x^n dx give
+// the power series of the transform's real and imaginary parts.
+bool sticky_constants(double eta, double tau, int nterms, double* ca, double* cb, double* hbc)
+{
+    const double om = 1.0 - eta;
+    const double qa = eta / 12.0, qb = tau + eta / om, qc = (1.0 + 0.5 * eta) / (om * om);
+    const double disc = qb * qb - 4.0 * qa * qc;
+    if (!(disc >= 0.0)) return false;
+    // the smaller root, written without cancellation
+    const double lam = 2.0 * qc / (qb + std::sqrt(disc));
+    const double mu = lam * eta * om;
+    const double a = (1.0 + 2.0 * eta - mu) / (om * om), b = (mu - 3.0 * eta) / (2.0 * om * om);
+    const double h = 0.5 * a, c0 = lam / 12.0 - h - b;
+    hbc[0] = h;
+    hbc[1] = b;
+    hbc[2] = c0;
+    const double e = 12.0 * eta;
+    double f = 1.0;  // n!
+    for (int n = 0; n < 2 * nterms; ++n) {
+        if (n > 0) f *= n;
+        const double mom = h / (n + 3) + b / (n + 2) + c0 / (n + 1);
+        const double sgn = ((n / 2) % 2) ? -1.0 : 1.0;
+        if (n % 2 == 0) ca[n / 2] = (n == 0 ? 1.0 : 0.0) - e * sgn * mom / f;
+        else cb[n / 2] = -e * sgn * mom / f;
+    }
+    return true;
+}
+
 // E[y^k] of the Schulz distribution: Gamma(a + k) / (Gamma(a) a^k), a = 1/p^2.
 double schulz_moment(double p, int k)
 {
@@ -321,7 +354,7 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
         return v;
     }
     case 13: case 14: case 15: case 16: case 17: case 18: case 19: case 20: case 21: case 22: case 23:
-    case 24: case 29: case 30: case 31: case 32: case 33: case 34: case 35: case 36: case 37: case 40:
+    case 24: case 29: case 30: case 31: case 32: case 33: case 34: case 35: case 36: case 37: case 40: case 49: case 50:
         return 1.0;  // shape-independent: no particles (the weight uses the cross-section)
     case 12: {
         // the box minus its cavity (monodisperse)

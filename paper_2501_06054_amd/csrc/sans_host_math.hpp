@@ -7,6 +7,12 @@ namespace host {
 double normal_quantile(double u);
 void gauss_legendre(int n, double* x, double* w);
 void py_series(double phi, int nterms, double* c, double* abg);
+// Baxter's adhesive hard spheres (volume fraction eta, stickiness tau): his
+// factor function on [0, 1] (units of the diameter) is the quadratic
+// h x^2 + b x + c0; hbc[0..2] = h, b, c0.  ca[m], cb[m]: coefficients of k^(2m)
+// in A(k) = 1 - 12 eta int Q cos(kx) and in B(k)/k = -12 eta int Q sin(kx)/k.
+// False when the adhesion parameter has no real solution.
+bool sticky_constants(double eta, double tau, int nterms, double* ca, double* cb, double* hbc);
 double schulz_moment(double p, int k);
 double positive_normal_quantile(double u, double p);
 double positive_normal_moment(double p, int k);

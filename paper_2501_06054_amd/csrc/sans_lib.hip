@@ -542,7 +542,9 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 45: batch_tile<45>(a, tl.first, tl.count, hist, tab); break;
         case 46: batch_tile<46>(a, tl.first, tl.count, hist, tab); break;
         case 47: batch_tile<47>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<48>(a, tl.first, tl.count, hist, tab); break;
+        case 48: batch_tile<48>(a, tl.first, tl.count, hist, tab); break;
+        case 49: batch_tile<49>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<50>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -824,6 +826,8 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(46)
         SANS_CASE(47)
         SANS_CASE(48)
+        SANS_CASE(49)
+        SANS_CASE(50)
     }
 #undef SANS_CASE
     return nullptr;
@@ -887,6 +891,8 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(46)
         SANS_CASE(47)
         SANS_CASE(48)
+        SANS_CASE(49)
+        SANS_CASE(50)
     }
 #undef SANS_CASE
     return nullptr;
@@ -947,6 +953,8 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(46)
         SANS_CASE(47)
         SANS_CASE(48)
+        SANS_CASE(49)
+        SANS_CASE(50)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1007,6 +1015,8 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(46)
         SANS_CASE(47)
         SANS_CASE(48)
+        SANS_CASE(49)
+        SANS_CASE(50)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1064,6 +1074,8 @@ PqFn pick_pq(int kind)
     case 46: return k_pq_avg<46>;
     case 47: return k_pq_avg<47>;
     case 48: return k_pq_avg<48>;
+    case 49: return k_pq_avg<49>;
+    case 50: return k_pq_avg<50>;
     }
     return nullptr;
 }
@@ -1111,7 +1123,8 @@ bool finite(double x) { return std::isfinite(x); }
 bool is_shape_independent(int kind)
 {
     return (kind >= SANS_GUINIER && kind <= SANS_GAUSS_LORENTZ_GEL)
-           || (kind >= SANS_SURFACE_FRACTAL && kind <= SANS_BROAD_PEAK) || kind == SANS_POLYMER_EXCL_VOLUME;
+           || (kind >= SANS_SURFACE_FRACTAL && kind <= SANS_BROAD_PEAK) || kind == SANS_POLYMER_EXCL_VOLUME
+           || kind == SANS_MASS_SURFACE_FRACTAL || kind == SANS_GEL_FIT;
 }
 
 // Isotropic sphere-based particles.
@@ -1133,7 +1146,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 48) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 50) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -1248,6 +1261,16 @@ int validate(const sans_params* p)
         if (p->kind == SANS_SPINODAL
             && !(p->extra[1] > 0.0 && finite(p->extra[1]) && p->extra[2] > 0.0 && p->extra[2] <= 10.0))
             return fail(SANS_E_INVALID_ARG, "spinodal: need q_max = extra[1] > 0 and 0 < gamma = extra[2] <= 10");
+        if (p->kind == SANS_MASS_SURFACE_FRACTAL
+            && !(p->extra[1] > 0.0 && p->extra[2] > 0.0 && p->extra[1] + p->extra[2] < 6.0
+                 && p->size[1] >= 0.0 && finite(p->size[1])))
+            return fail(SANS_E_INVALID_ARG, "mass-surface fractal: need Dm = extra[1] > 0, Ds = extra[2] > 0, "
+                                            "Dm + Ds < 6 and a primary radius size[1] >= 0");
+        if (p->kind == SANS_GEL_FIT
+            && !(p->extra[2] > 0.0 && p->extra[2] <= 6.0 && p->extra[1] >= 0.0 && finite(p->extra[1])
+                 && p->size[1] >= 0.0 && finite(p->size[1])))
+            return fail(SANS_E_INVALID_ARG, "gel: need dimension extra[2] in (0, 6], a Guinier scale "
+                                            "extra[1] >= 0 and a radius size[1] >= 0");
         if (p->poly > 0.0) return fail(SANS_E_UNSUPPORTED, "shape-independent model: no size distribution");
         if (p->sq_phi > 0.0) return fail(SANS_E_UNSUPPORTED, "shape-independent model: no structure factor");
     }
@@ -1280,6 +1303,47 @@ int validate(const sans_params* p)
     if (!(p->phi >= 0.0 && p->phi < 1.0)) return fail(SANS_E_INVALID_ARG, "phi must be in [0, 1)");
     if (!(p->sq_phi >= 0.0 && p->sq_phi < 0.6)) return fail(SANS_E_INVALID_ARG, "sq_phi must be in [0, 0.6)");
     if (p->sq_phi > 0.0 && !(p->sq_radius > 0.0)) return fail(SANS_E_INVALID_ARG, "sq_radius must be > 0");
+    if (p->sq_kind < SANS_SQ_HARD_SPHERE || p->sq_kind > SANS_SQ_SQUARE_WELL)
+        return fail(SANS_E_UNSUPPORTED, "unknown sq_kind");
+    if (p->sq_phi > 0.0 && p->sq_kind == SANS_SQ_STICKY_HARD_SPHERE) {
+        if (!(p->sq_extra[0] > 0.0 && finite(p->sq_extra[0])))
+            return fail(SANS_E_INVALID_ARG, "adhesive spheres: stickiness sq_extra[0] must be > 0");
+        double ca[kPySeriesTerms], cb[kPySeriesTerms], hbc[3];
+        if (!host::sticky_constants(p->sq_phi, p->sq_extra[0], kPySeriesTerms, ca, cb, hbc))
+            return fail(SANS_E_DOMAIN, "adhesive spheres: no solution at this stickiness and volume fraction");
+    }
+    if (p->sq_phi > 0.0 && p->sq_kind == SANS_SQ_SQUARE_WELL) {
+        if (!(finite(p->sq_extra[0]) && p->sq_extra[1] >= 1.0 && p->sq_extra[1] <= 4.0))
+            return fail(SANS_E_INVALID_ARG, "square well: need a finite depth sq_extra[0] and a width sq_extra[1] in [1, 4]");
+        // 1/S must stay positive on the instrument's q range (FP64 scan of
+        // x = 2 q R from 0 to past the largest q of the cone)
+        const double lmin = p->lambda0 * (1.0 - p->dlambda_rel);
+        const double qmax = 4.0 * kPi / lmin * std::sin(0.5 * p->cone_alpha);
+        const double xmax = 2.0 * p->sq_radius * qmax * 1.01;
+        double c[kPySeriesTerms], abg[3];
+        host::py_series(p->sq_phi, kPySeriesTerms, c, abg);
+        const double w = p->sq_extra[1], d8 = 8.0 * p->sq_phi * p->sq_extra[0];
+        auto phi3 = [](double y) {
+            if (y < 1e-3) return 1.0 - y * y / 10.0;
+            return 3.0 * (std::sin(y) - y * std::cos(y)) / (y * y * y);
+        };
+        for (int i = 0; i <= 4096; ++i) {
+            const double x = xmax * i / 4096.0;
+            double gx;
+            if (x < 1.0) {
+                gx = 0.0;
+                for (int m = kPySeriesTerms - 1; m >= 0; --m) gx = gx * x * x + c[m];
+            } else {
+                const double sx = std::sin(x), cx = std::cos(x), x2 = x * x;
+                gx = (abg[0] * (sx - x * cx) / x2 + abg[1] * (2.0 * x * sx + (2.0 - x2) * cx - 2.0) / (x2 * x)
+                      + abg[2] * (-x2 * x2 * cx + 4.0 * ((3.0 * x2 - 6.0) * cx + (x2 * x - 6.0 * x) * sx + 6.0))
+                            / (x2 * x2 * x)) / x;
+            }
+            const double inv = 1.0 + 24.0 * p->sq_phi * gx - d8 * (w * w * w * phi3(w * x) - phi3(x));
+            if (!(inv > 1e-6))
+                return fail(SANS_E_DOMAIN, "square well: 1/S(q) <= 0 inside the instrument's q range");
+        }
+    }
     if (!(p->poly >= 0.0 && p->poly <= 1.0)) return fail(SANS_E_INVALID_ARG, "poly must be in [0, 1]");
     if (p->poly > 0.0 && p->poly < 1e-4) return fail(SANS_E_INVALID_ARG, "poly must be 0 or >= 1e-4");
     if (p->poly_mask < 0 || p->poly_mask > 7) return fail(SANS_E_INVALID_ARG, "poly_mask must be in 0..7");
@@ -1491,6 +1555,20 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
             a.si_d = p->size[0];
             a.si_e = p->size[1];
             break;
+        case SANS_MASS_SURFACE_FRACTAL: {
+            const double pm = 0.5 * e1, ps = 0.5 * (6.0 - e2 - e1);
+            a.si_a = 1.0 / (3.0 * pm);
+            a.si_b = pm;
+            a.si_c = p->size[1] * p->size[1] / (3.0 * ps);
+            a.si_d = ps;
+            break;
+        }
+        case SANS_GEL_FIT:
+            a.si_a = (e2 + 1.0) / 3.0;
+            a.si_b = 0.5 * e2;
+            a.si_c = e1;
+            a.si_d = p->size[1] * p->size[1] / 3.0;
+            break;
         case SANS_POLYMER_EXCL_VOLUME:
             a.si_a = (2.0 * e1 + 1.0) * (2.0 * e1 + 2.0) / 6.0;
             a.si_b = e1;
@@ -1554,6 +1632,25 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
         a.py_gamma = (float)abg[2];
         a.sq_2r = (float)(2.0 * p->sq_radius);
         a.sq_24phi = (float)(24.0 * p->sq_phi);
+        a.sq_kind = p->sq_kind;
+        if (p->sq_kind == SANS_SQ_STICKY_HARD_SPHERE) {
+            double ca[kPySeriesTerms], cb[kPySeriesTerms], hbc[3];
+            host::sticky_constants(p->sq_phi, p->sq_extra[0], kPySeriesTerms, ca, cb, hbc);
+            for (int k = 0; k < kPySeriesTerms; ++k) {
+                a.sh_ca[k] = (float)ca[k];
+                a.sh_cb[k] = (float)cb[k];
+            }
+            a.sh_e = (float)(12.0 * p->sq_phi);
+            a.sh_h = (float)hbc[0];
+            a.sh_b = (float)hbc[1];
+            a.sh_c0 = (float)hbc[2];
+        }
+        if (p->sq_kind == SANS_SQ_SQUARE_WELL) {
+            const double w = p->sq_extra[1];
+            a.sw_8de = (float)(8.0 * p->sq_phi * p->sq_extra[0]);
+            a.sw_w = (float)w;
+            a.sw_w3 = (float)(w * w * w);
+        }
     }
     a.M = p->table_size;
 }

@@ -15,7 +15,7 @@ import torch  # loaded first so that libsans shares PyTorch's HIP runtime
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsans.so")
 
-SANS_ABI_VERSION = 3
+SANS_ABI_VERSION = 4
 SANS_OK = 0
 SANS_E_INVALID_ARG = -1
 SANS_E_UNSUPPORTED = -2
@@ -35,7 +35,9 @@ KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelep
         "line": 34, "two_lorentzian": 35, "correlation_length": 36, "broad_peak": 37, "fractal": 38,
         "fractal_core_shell": 39, "polymer_excl_volume": 40, "elliptical_cylinder": 41,
         "core_shell_bicelle": 42, "core_shell_parallelepiped": 43, "core_shell_bicelle_elliptical": 44,
-        "stacked_disks": 45, "sc_paracrystal": 46, "bcc_paracrystal": 47, "fcc_paracrystal": 48}
+        "stacked_disks": 45, "sc_paracrystal": 46, "bcc_paracrystal": 47, "fcc_paracrystal": 48,
+        "mass_surface_fractal": 49, "gel_fit": 50}
+SQ_KIND = {"hard_sphere": 0, "sticky_hard_sphere": 1, "square_well": 2}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 POLY_KIND = {"schulz": 0, "gaussian": 1}
@@ -62,8 +64,8 @@ class sans_params(C.Structure):
         ("sample_w", C.c_double), ("sample_h", C.c_double), ("sample_d", C.c_double),
         ("det_w", C.c_double), ("det_h", C.c_double), ("det_z", C.c_double),
         ("nx", C.c_int32), ("ny", C.c_int32), ("quad_n", C.c_int32), ("tally", C.c_int32),
-        ("poly_kind", C.c_int32), ("reserved", C.c_int32),
-        ("extra", C.c_double * 4),
+        ("poly_kind", C.c_int32), ("sq_kind", C.c_int32),
+        ("extra", C.c_double * 4), ("sq_extra", C.c_double * 2),
     ]
 
 
@@ -167,6 +169,9 @@ def to_params(p: dict, tally: str = "auto") -> sans_params:
     s.poly_kind = POLY_KIND[p.get("poly_kind", "schulz")]
     for k, v in enumerate(p.get("extra", (0.0, 0.0, 0.0, 0.0))):
         s.extra[k] = float(v)
+    s.sq_kind = SQ_KIND[p.get("sq_kind", "hard_sphere")]
+    for k, v in enumerate(p.get("sq_extra", (0.0, 0.0))):
+        s.sq_extra[k] = float(v)
     return s
 
 

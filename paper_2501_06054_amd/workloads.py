@@ -298,6 +298,26 @@ def oriented_fcc_paracrystal() -> dict:
                               orient_sigma=(3 * DEG, 3 * DEG, 3 * DEG), nx=256, ny=256))
 
 
+def sticky_coreshell() -> dict:
+    """The core-shell spheres of the default workload (Schulz core radius 40
+    A, sigma/mean 0.2, 10 A shell) as adhesive spheres: Baxter's S(Q) at
+    volume fraction 0.1, radius 50 A, stickiness 0.2; 256x256, 1e8 neutrons."""
+    return dict(name="sticky_coreshell", n=10**8, seed=24, exp_id=0,
+                params=params(kind="core_shell", size=(40.0, 0, 0), shell=10.0,
+                              sld=(1e-6, 3e-6, 6.3e-6), phi=0.1, sq_phi=0.1, sq_radius=50.0,
+                              sq_kind="sticky_hard_sphere", sq_extra=(0.2, 0.0),
+                              poly=0.2, poly_mask=1, nx=256, ny=256))
+
+
+def mass_surface_fractal() -> dict:
+    """Mass-surface fractal: clusters of mass dimension 1.8 and radius of
+    gyration 300 A made of primary particles of radius of gyration 25 A with
+    surface dimension 2.3, I(0) = 40 / cm, 256x256, 1e9 neutrons."""
+    return dict(name="mass_surface_fractal", n=10**9, seed=25, exp_id=0,
+                params=params(kind="mass_surface_fractal", size=(300.0, 25.0, 0.0), extra=(40.0, 1.8, 2.3, 0.0),
+                              nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -321,6 +341,8 @@ WORKLOADS = {
     "polymer_excl_volume": polymer_excl_volume,
     "oriented_elliptical_cylinder": oriented_elliptical_cylinder,
     "oriented_fcc_paracrystal": oriented_fcc_paracrystal,
+    "sticky_coreshell": sticky_coreshell,
+    "mass_surface_fractal": mass_surface_fractal,
 }
 
 

@@ -149,6 +149,20 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
      "SANS_E_INVALID_ARG"),
     (dict(kind="stacked_disks", size=(10.0, 20.0, 0.0), shell=1.0, extra=(2.5, 1.0, 0, 0)), "SANS_E_INVALID_ARG"),
     (dict(kind="fcc_paracrystal", size=(10.0, 50.0, 0.0), extra=(0.0, 0, 0, 0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="mass_surface_fractal", size=(100.0, 5.0, 0.0), extra=(1.0, 3.0, 3.0, 0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="mass_surface_fractal", size=(100.0, -5.0, 0.0), extra=(1.0, 2.0, 2.0, 0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="gel_fit", size=(30.0, 100.0, 0.0), extra=(1.0, 0.5, 0.0, 0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="gel_fit", size=(30.0, 100.0, 0.0), extra=(1.0, -0.5, 2.0, 0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="sphere", sq_phi=0.2, sq_radius=50.0, sq_kind="sticky_hard_sphere", sq_extra=(0.0, 0.0)),
+     "SANS_E_INVALID_ARG"),
+    # below Baxter's two-phase boundary: no real adhesion parameter
+    (dict(kind="sphere", sq_phi=0.12, sq_radius=50.0, sq_kind="sticky_hard_sphere", sq_extra=(0.05, 0.0)),
+     "SANS_E_DOMAIN"),
+    (dict(kind="sphere", sq_phi=0.2, sq_radius=50.0, sq_kind="square_well", sq_extra=(1.0, 0.9)),
+     "SANS_E_INVALID_ARG"),
+    # a deep, wide well drives 1/S(0) below zero
+    (dict(kind="sphere", sq_phi=0.2, sq_radius=50.0, sq_kind="square_well", sq_extra=(3.0, 2.0)),
+     "SANS_E_DOMAIN"),
 ])
 def test_capped_body_params_rejected_without_gpu(S, over, code):
     from paper_2501_06054_amd import workloads as W
@@ -160,6 +174,14 @@ def test_capped_body_params_rejected_without_gpu(S, over, code):
 def test_unknown_kind_rejected_without_gpu(S):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=1.0))
-    sp.kind = 49
+    sp.kind = 51
+    h = C.c_void_p()
+    assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED
+
+
+def test_unknown_structure_factor_rejected_without_gpu(S):
+    from paper_2501_06054_amd import workloads as W
+    sp = S.to_params(W.params(kind="sphere", sq_phi=0.1, sq_radius=50.0))
+    sp.sq_kind = 3
     h = C.c_void_p()
     assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED

@@ -287,6 +287,19 @@ PER_NEUTRON = {
                                      orient_kind="isotropic", poly=0.1), 30011),
     "quad_bcc_paracrystal": (W.params(kind="bcc_paracrystal", mode="quad", size=(30, 160, 0),
                                       extra=(0.1, 0, 0, 0), orient_kind="isotropic", quad_n=40), 301),
+    # the last shape-independent models; adhesive and square-well structure factors
+    "mass_surface_fractal": (W.workload("mass_surface_fractal")["params"], 50021),
+    "gel_fit": (W.params(kind="gel_fit", size=(40.0, 150.0, 0), extra=(3.0, 0.5, 1.7, 0)), 30011),
+    "sticky_coreshell": (W.workload("sticky_coreshell")["params"], 50021),
+    "square_well_poly_sphere": (W.params(kind="sphere", size=(40.0, 0, 0), sld=(1e-6, 0, 0), phi=0.15, poly=0.1,
+                                         sq_phi=0.15, sq_radius=42.0, sq_kind="square_well",
+                                         sq_extra=(1.0, 1.4)), 30011),
+    "quad_sticky_cylinder": (W.params(kind="cylinder", mode="quad", size=(20.0, 80.0, 0), orient_kind="isotropic",
+                                      sq_phi=0.1, sq_radius=30.0, sq_kind="sticky_hard_sphere",
+                                      sq_extra=(0.3, 0.0)), 601),
+    "repulsive_shoulder_cylinder": (W.params(kind="cylinder", size=(20.0, 120.0, 0), orient_kind="isotropic",
+                                             sq_phi=0.2, sq_radius=35.0, sq_kind="square_well",
+                                             sq_extra=(-0.8, 1.6)), 30011),
 }
 
 
@@ -315,7 +328,8 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "oriented_hollow_prism_thick", "teubner_strey", "poly_gauss_coil", "dab", "mass_fractal",
              "star_polymer", "gaussian_peak", "multilayer_vesicle", "linear_pearls_poly", "spinodal",
              "fractal_poly", "polymer_excl_volume", "broad_peak", "oriented_elliptical_cylinder",
-             "bicelle_poly_iso", "cs_parallelepiped_gauss", "stacked_disks_gauss", "oriented_fcc_paracrystal"]
+             "bicelle_poly_iso", "cs_parallelepiped_gauss", "stacked_disks_gauss", "oriented_fcc_paracrystal",
+             "mass_surface_fractal", "gel_fit", "sticky_coreshell", "square_well_poly_sphere"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -450,7 +464,7 @@ def test_full_size_coreshell(S):
 
 @pytest.mark.parametrize("name", ["oriented_cylinder", "oriented_ellipsoid", "oriented_barbell",
                                   "oriented_hollow_prism", "micelle_py", "oriented_core_shell_cylinder",
-                                  "teubner_strey"])
+                                  "teubner_strey", "sticky_coreshell", "mass_surface_fractal"])
 def test_full_size_sampled(S, name):
     """1e9- and 1e8-neutron workloads: the full run equals the sum of its chunks, and
     windows spread over the whole index range match the oracle neutron by
