@@ -70,7 +70,8 @@ typedef struct {
                               47 body-centred, 48 face-centred cubic
                               paracrystals of spheres; shape-independent:
                               49 mass-surface fractal, 50 gel (fractal
-                              network plus frozen inhomogeneities)          */
+                              network plus frozen inhomogeneities);
+                              oriented: 51 superball                        */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -543,6 +544,40 @@ static double caps_volume(const double s[3], int barbell)
     return 2.0 * ORC_PI * r * r * r * ((1.0 - t0) - (1.0 - t0 * t0 * t0) / 3.0);
 }
 
+/* Superball |x|^(2p) + |y|^(2p) + |z|^(2p) <= R^(2p) (Tables I-II, group F;
+ * p = 1/2 octahedron, 1 sphere, p -> infinity the cube of edge 2R), axes
+ * x, y, z along A, B, C.  Its transform, even in each coordinate, is
+ *   8 int_0^R dx cos(Q_A x) int_0^ym(x) dy cos(Q_B y) sin(Q_C zm)/Q_C,
+ * ym(x) = (R^2p - x^2p)^(1/2p), zm(x, y) = (R^2p - x^2p - y^2p)^(1/2p): the z
+ * integral exact, x and y by n-point Gauss-Legendre on [0, R] and
+ * [0, ym(x)].  Volume 8 R^3 Gamma(1 + 1/2p)^3 / Gamma(1 + 3/2p). */
+static double superball_amplitude(double R, double p, double qa, double qb, double qc, int n)
+{
+    const double *gx, *gw;
+    cap_nodes(n, &gx, &gw);
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double x = 0.5 * R * (gx[i] + 1.0);
+        double ym = R * pow(1.0 - pow(x / R, 2.0 * p), 1.0 / (2.0 * p));
+        double inner = 0.0;
+        for (int j = 0; j < n; ++j) {
+            double y = 0.5 * ym * (gx[j] + 1.0);
+            double rest = 1.0 - pow(x / R, 2.0 * p) - pow(y / R, 2.0 * p);
+            double zm = rest > 0.0 ? R * pow(rest, 1.0 / (2.0 * p)) : 0.0;
+            double zint = zm * orc_sinc(qc * zm); /* sin(Q_C zm)/Q_C */
+            inner += 0.5 * ym * gw[j] * cos(qb * y) * zint;
+        }
+        sum += 0.5 * R * gw[i] * cos(qa * x) * inner;
+    }
+    return 8.0 * sum;
+}
+
+static double superball_volume(double R, double p)
+{
+    double g1 = tgamma(1.0 + 1.0 / (2.0 * p));
+    return 8.0 * R * R * R * g1 * g1 * g1 / tgamma(1.0 + 3.0 / (2.0 * p));
+}
+
 /* Unit-contrast amplitudes of the homogeneous bodies the layered models are
  * built from: a cylinder (radius r, length len, axis C), an ellipsoid
  * (semi-axes a, b, c along A, B, C) and a box (edges a, b, c). */
@@ -632,6 +667,8 @@ static double amplitude(int kind, const double s[3], double shell, const double 
     case 12: /* hollow prism, walls of thickness shell: the box minus its cavity */
         return drho * (box_amp(s[0], s[1], s[2], qa, qb, qc)
                        - box_amp(s[0] - 2.0 * shell, s[1] - 2.0 * shell, s[2] - 2.0 * shell, qa, qb, qc));
+    case 51: /* superball: half-edge s0, exponent parameter p = extra[0] */
+        return drho * superball_amplitude(s[0], extra[0], qa, qb, qc, cap_n);
     case 41: { /* elliptical cylinder: semi-axes s0 along A, s1 along B, length s2
                   along C; the ellipse's transform is the disc's at the scaled
                   projection sqrt((s0 Q_A)^2 + (s1 Q_B)^2) */
@@ -988,7 +1025,7 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
 }
 
 /* Orientation matters (the particles from 2 to 12 but the micelle). */
-static int anisotropic(int kind) { return (kind >= 2 && kind != 8 && kind <= 12) || (kind >= 41 && kind <= 48); }
+static int anisotropic(int kind) { return (kind >= 2 && kind != 8 && kind <= 12) || (kind >= 41 && kind <= 48) || kind == 51; }
 
 /* Sizes scaled by the relative size draw y according to the mask. */
 static void scaled_sizes(const orc_params* p, double y, double s[3])
@@ -1077,6 +1114,8 @@ double orc_mean_volume(const orc_params* p)
     case 6: /* all three sizes scale together (or none): V(y) = V(1) y^3 */
         return (ORC_PI * s[0] * s[0] * s[1] + caps_volume(s, p->kind == 5))
              * size_moment(p, p->poly_mask == 7 ? 3 : 0);
+    case 51:
+        return superball_volume(s[0], p->extra[0]) * size_moment(p, b0 ? 3 : 0);
     case 25: /* fuzzy sphere: the sphere's volume */
         return vol_sphere(s[0]) * size_moment(p, b0 ? 3 : 0);
     case 26: { /* vesicle: the shell, 4/3 pi ((R y + t)^3 - (R y)^3) */

@@ -1524,3 +1524,46 @@ def test_square_well_closed_form_and_limits(orc, eta, depth, width):
         assert orc.square_well_sq(q, R, eta, depth, 1.0) == pytest.approx(orc.py_sq(q, R, eta), rel=1e-15)
     s0 = 1 / ((1 + 2 * eta) ** 2 / (1 - eta) ** 4 - 8 * eta * depth * (width ** 3 - 1))
     assert orc.square_well_sq(0.0, R, eta, depth, width) == pytest.approx(s0, rel=1e-12)
+
+
+# ---------------------------------------------------------------- superball
+
+def _superball_F(orc, p, n, qv, R=30.0):
+    pp = W.params(kind="superball", size=(R, 0.0, 0.0), sld=(1.0, 0.0, 0.0), extra=(p, 0.0, 0.0, 0.0), quad_n=n)
+    return orc.amplitude(pp, math.sqrt(sum(x * x for x in qv)), qv)
+
+
+@pytest.mark.parametrize("qv", [(0.0, 0.0, 0.0), (0.03, 0.05, 0.07), (0.11, 0.0, 0.02), (0.0, 0.0, 0.15)])
+def test_superball_at_p1_is_the_sphere(orc, qv):
+    R = 30.0
+    x = R * math.sqrt(sum(c * c for c in qv))
+    sph = 4 / 3 * math.pi * R ** 3 * (3 * (math.sin(x) - x * math.cos(x)) / x ** 3 if x > 0 else 1.0)
+    # (qR = 4.5 sits next to the sphere's first zero: the bar is relative to F(0))
+    assert _superball_F(orc, 1.0, 300, qv) == pytest.approx(sph, abs=2e-8 * 4 / 3 * math.pi * R ** 3)
+
+
+def test_superball_volumes_and_limits(orc):
+    """F(0) is the volume: 8 R^3 Gamma(1 + 1/2p)^3 / Gamma(1 + 3/2p) (the
+    octahedron's 4 R^3 / 3 at p = 1/2); large p tends to the cube of edge 2R
+    (the transform of the box); the exact transform is symmetric under
+    permutations of the axes."""
+    R = 30.0
+    assert _superball_F(orc, 0.5, 300, (0.0, 0.0, 0.0)) == pytest.approx(4 / 3 * R ** 3, rel=1e-12)
+    for p in (0.7, 2.0, 5.0):
+        g = math.gamma(1 + 1 / (2 * p))
+        assert _superball_F(orc, p, 300, (0.0, 0.0, 0.0)) == pytest.approx(8 * R ** 3 * g ** 3 / math.gamma(1 + 3 / (2 * p)),
+                                                                            rel=1e-7)
+    qv = (0.03, 0.05, 0.07)
+    box = 8 * R ** 3 * math.prod(math.sin(c * R) / (c * R) for c in qv)
+    assert _superball_F(orc, 1000.0, 300, qv) == pytest.approx(box, rel=2e-6)
+    a = _superball_F(orc, 2.0, 300, (0.02, 0.05, 0.08))
+    for perm in ((0.08, 0.02, 0.05), (0.05, 0.08, 0.02)):
+        assert _superball_F(orc, 2.0, 300, perm) == pytest.approx(a, rel=1e-6)
+
+
+def test_superball_mean_volume(orc):
+    p = W.params(kind="superball", size=(30.0, 0.0, 0.0), extra=(2.0, 0.0, 0.0, 0.0), poly=0.2, poly_mask=1)
+    g = math.gamma(1 + 1 / 4.0)
+    z = 1 / 0.2 ** 2
+    y3 = (z + 1) * (z + 2) / z ** 2     # <y^3> of the Schulz distribution of mean 1
+    assert orc.mean_volume(p) == pytest.approx(8 * 30.0 ** 3 * g ** 3 / math.gamma(1 + 3 / 4.0) * y3, rel=1e-12)
