@@ -87,6 +87,8 @@ STEP = {
     "py_sq":         ((15,  0,  0,  0, 1, 0), 25),  # A10: series in x^2, 1/(1 + 24 phi G/x)
     "sticky_sq":     ((27,  0,  0,  0, 1, 0), 50),  # adhesive spheres: two series in k^2, A^2 + B^2, reciprocal
     "msf_I":         ((8,   0,  0,  3, 3, 0), 10),  # mass-surface fractal: two log2, one exp2
+    "sb_row":        ((16,  3,  0,  0, 0, 0), 22),  # superball, per x node: cos(Q_A R x), the row's sum
+    "sb_node":       ((32,  6,  0,  0, 0, 0), 44),  # superball, per (x, y) node: cos(Q_B R y), sin(Q_C R zm)/Q_C R
     "weight":        ((3,   0,  0,  2, 0, 0), 3),   # A11
     "detector":      ((0,   5,  0, 23, 0, 1), 0),   # A12: plane crossing (quotient), pixel
     "tally":         ((0,   2,  0,  0, 0, 0), 0),   # A13: address; the add itself is a memory op
@@ -132,6 +134,9 @@ PATHS = {
     "sticky_coreshell": COMMON + ["philox_block"] * 3 + ["uniform"] * 9
                         + ["size_draw", "core_shell_F", "sticky_sq"],
     "mass_surface_fractal": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["msf_I"],
+    # superball: the 24 x 24 rule of the workload
+    "oriented_superball": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
+                          + ["qvec"] + ["orient_angle"] * 3 + ["project_abc"] + ["sb_row"] * 24 + ["sb_node"] * 576,
 }
 # Exact-average paths, per quadrature node (76 x 76 = 5776 nodes per neutron),
 # all FP32:

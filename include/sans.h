@@ -180,11 +180,18 @@ typedef enum {
                                     radius of gyration size[1] >= 0:
                                     (1 + (qL)^2/(3 pm))^-pm (1 + (q size[1])^2/(3 ps))^-ps,
                                     pm = Dm/2 > 0, ps = (6 - Ds - Dm)/2 > 0    */
-    SANS_GEL_FIT = 50            /* network of mesh size L and dimension D =
+    SANS_GEL_FIT = 50,           /* network of mesh size L and dimension D =
                                     extra[2] in (0, 6]:
                                     extra[0] (1 + (D + 1)/3 (qL)^2)^(-D/2),
                                     plus frozen inhomogeneities extra[1]
                                     exp(-(q size[1])^2/3), size[1] >= 0       */
+    /* Oriented superball (Tables I-II, group F): |x|^2p + |y|^2p + |z|^2p <=
+     * R^2p with x, y, z along A, B, C; R = size[0], p = extra[0] in
+     * [0.25, 10000] (1/2 octahedron, 1 sphere, large p a cube of edge 2R).
+     * Its transform is integrated over x and y by quad_n-point Gauss-Legendre
+     * rules (quad_n^2 nodes per event, in every mode), over z exactly;
+     * SANS_MODE_QUAD is not provided (quad_n^2 nodes per orientation node). */
+    SANS_SUPERBALL = 51
 } sans_kind;
 
 /* Structure factor S(q) of the particles (when sq_phi > 0): volume fraction

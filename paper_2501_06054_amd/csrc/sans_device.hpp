@@ -53,6 +53,13 @@ template <int M> struct CosD { static constexpr double v = cos_coef(M); };
 
 constexpr int kPySeriesTerms = 12;
 constexpr int kMaxQuad = 256;
+// Structure-factor constants in device memory: the adhesive spheres' series
+// of A(k) and B(k)/k in k^2 [kPySeriesTerms each], then 12 eta and the factor
+// function's coefficients h, b, c0 (h x^2 + b x + c0); the square well's
+// 8 eta depth, width, width^3.
+constexpr int kSqA = 0, kSqB = kPySeriesTerms, kSqE = 2 * kPySeriesTerms, kSqH = kSqE + 1, kSqBb = kSqE + 2,
+              kSqC0 = kSqE + 3, kSqW8 = kSqE + 4, kSqW = kSqE + 5, kSqW3 = kSqE + 6, kSqCoef = kSqE + 7;
+
 // orientation node arrays of the exact average: mu, w_mu, cos beta, sin beta,
 // w_beta, sqrt(1 - mu^2)
 constexpr int kQuadArrays = 6;
@@ -84,12 +91,9 @@ struct TraceArgs {
     float sq_2r, sq_24phi;
     float py_alpha, py_beta, py_gamma;
     float py_c[kPySeriesTerms];
-    // adhesive hard spheres: series of A(k) and B(k)/k in k^2, 12 eta and the
-    // factor function's coefficients h, b, c0 (h x^2 + b x + c0)
-    float sh_ca[kPySeriesTerms], sh_cb[kPySeriesTerms];
-    float sh_e, sh_h, sh_b, sh_c0;
-    // square well: 8 eta depth, width, width^3
-    float sw_8de, sw_w, sw_w3;
+    // adhesive and square-well constants (device memory, kSqCoef floats; read
+    // only on their branch, so they hold no registers in the other kernels)
+    const float* sq_coef;
     // tables (device global memory, FP64 knots; kernels stage them in LDS)
     int32_t M;                    // knots per table
     const double* tab_size;       // Schulz quantiles or nullptr
@@ -418,32 +422,33 @@ __device__ __forceinline__ float py_inv_sq(const TraceArgs& a, float x)
 // imaginary parts of 1 - 12 eta int_0^1 Q(x) exp(i k x) dx, k = q sigma, Q
 // the quadratic factor function; power series in k^2 below k = 2.5, above
 // the closed forms of int x^n cos(kx) and int x^n sin(kx) (n = 0, 1, 2).
-__device__ __forceinline__ float sticky_sq(const TraceArgs& a, float k)
+__device__ __forceinline__ float sticky_sq(const float* __restrict__ c, float k)
 {
     float A, B;
     if (k < 2.5f) {
         const float k2 = k * k;
-        float ra = a.sh_ca[kPySeriesTerms - 1], rb = a.sh_cb[kPySeriesTerms - 1];
+        float ra = c[kSqA + kPySeriesTerms - 1], rb = c[kSqB + kPySeriesTerms - 1];
 #pragma unroll
         for (int m = kPySeriesTerms - 2; m >= 0; --m) {
-            ra = __builtin_fmaf(ra, k2, a.sh_ca[m]);
-            rb = __builtin_fmaf(rb, k2, a.sh_cb[m]);
+            ra = __builtin_fmaf(ra, k2, c[kSqA + m]);
+            rb = __builtin_fmaf(rb, k2, c[kSqB + m]);
         }
         A = ra;
         B = rb * k;
     } else {
-        float s, c;
-        sincos_f(k, s, c);
+        float s, cs;
+        sincos_f(k, s, cs);
         const float ik = rcpf(k);
-        const float ks = k * s, kc = k * c;
+        const float ks = k * s, kc = k * cs;
         const float c0 = s * ik;
-        const float c1 = (ks + c - 1.0f) * ik * ik;
+        const float c1 = (ks + cs - 1.0f) * ik * ik;
         const float c2 = __builtin_fmaf(k, ks, 2.0f * (kc - s)) * ik * ik * ik;
-        const float s0 = (1.0f - c) * ik;
+        const float s0 = (1.0f - cs) * ik;
         const float s1 = (s - kc) * ik * ik;
-        const float s2 = (__builtin_fmaf(-k, kc, 2.0f * (ks + c)) - 2.0f) * ik * ik * ik;
-        A = __builtin_fmaf(-a.sh_e, __builtin_fmaf(a.sh_h, c2, __builtin_fmaf(a.sh_b, c1, a.sh_c0 * c0)), 1.0f);
-        B = a.sh_e * __builtin_fmaf(a.sh_h, s2, __builtin_fmaf(a.sh_b, s1, a.sh_c0 * s0));
+        const float s2 = (__builtin_fmaf(-k, kc, 2.0f * (ks + cs)) - 2.0f) * ik * ik * ik;
+        const float h = c[kSqH], b = c[kSqBb], q0 = c[kSqC0];
+        A = __builtin_fmaf(-c[kSqE], __builtin_fmaf(h, c2, __builtin_fmaf(b, c1, q0 * c0)), 1.0f);
+        B = c[kSqE] * __builtin_fmaf(h, s2, __builtin_fmaf(b, s1, q0 * s0));
     }
     return rcpf(__builtin_fmaf(A, A, B * B));
 }
@@ -455,9 +460,12 @@ __device__ __forceinline__ float sticky_sq(const TraceArgs& a, float k)
 __device__ __forceinline__ float struct_factor(const TraceArgs& a, float q)
 {
     const float x = q * a.sq_2r;
-    if (a.sq_kind == 1) return sticky_sq(a, x);
+    if (a.sq_kind == 1) return sticky_sq(a.sq_coef, x);
     float inv = py_inv_sq(a, x);
-    if (a.sq_kind == 2) inv = __builtin_fmaf(-a.sw_8de, __builtin_fmaf(a.sw_w3, sph3j_f(a.sw_w * x), -sph3j_f(x)), inv);
+    if (a.sq_kind == 2) {
+        const float* __restrict__ c = a.sq_coef;
+        inv = __builtin_fmaf(-c[kSqW8], __builtin_fmaf(c[kSqW3], sph3j_f(c[kSqW] * x), -sph3j_f(x)), inv);
+    }
     return rcpf(inv);
 }
 
@@ -551,7 +559,7 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kFractalCoreShell = 39, kPolymerExclVolume = 40, kEllipticalCylinder = 41,
               kCoreShellBicelle = 42, kCoreShellParallelepiped = 43, kCoreShellBicelleElliptical = 44,
               kStackedDisks = 45, kScParacrystal = 46, kBccParacrystal = 47, kFccParacrystal = 48,
-              kMassSurfaceFractal = 49, kGelFit = 50 };
+              kMassSurfaceFractal = 49, kGelFit = 50, kSuperball = 51 };
 
 // F^2 multiplied by an orientation-dependent interference factor (stacked
 // disks, paracrystals).
@@ -575,7 +583,7 @@ constexpr bool kSphereFamily = (KIND >= kFuzzySphere && KIND <= kLinearPearls) |
 // thick hollow prism, but the micelle).
 template <int KIND>
 constexpr bool kAniso = (KIND >= kCylinder && KIND <= kHollowPrismThick && KIND != kMicelle)
-                        || (KIND >= kEllipticalCylinder && KIND <= kFccParacrystal);
+                        || (KIND >= kEllipticalCylinder && KIND <= kFccParacrystal) || KIND == kSuperball;
 
 // Bodies of revolution about C: cylinders (plain, hollow, core-shell),
 // barbell, capped cylinder (only the axis projection Q.C and Q_AB enter, the
@@ -605,6 +613,41 @@ __device__ __forceinline__ float caps_sum(const TraceArgs& a, float sP, float cP
         sincos_f(B * tn[i], sv, cv);
         const float c = __builtin_fmaf(cP, cv, -(sP * sv));
         sum = __builtin_fmaf(wn[i] * c, lambda1_f(X * sn[i]), sum);
+    }
+    return sum;
+}
+
+// The superball's transform at unit size and contrast, given the phases per
+// unit length times the size, ta = Q_A R, tb = Q_B R, tc = Q_C R: the nested
+// Gauss-Legendre rule over the octant's x and y (host nodes, [n + 3 n^2]
+// floats: x_i, then y_ij, zm_ij and the weights), the z integral
+// sin(tc zm)/tc exact (its series below |tc| = 1e-2).
+__device__ __forceinline__ float superball_sum(const TraceArgs& a, float ta, float tb, float tc)
+{
+    const int n = a.cap_n;
+    const float* __restrict__ xs = a.cap_nodes;
+    const float* __restrict__ ys = xs + n;
+    const float* __restrict__ zs = ys + n * n;
+    const float* __restrict__ ws = zs + n * n;
+    const bool small = fabsf(tc) < 1e-2f;
+    const float itc = small ? 0.0f : rcpf(tc);
+    const float tc2 = tc * tc * (-1.0f / 6.0f);
+    float sum = 0.0f;
+    for (int i = 0; i < n; ++i) {
+        float sx, cx;
+        sincos_f(ta * xs[i], sx, cx);
+        float inner = 0.0f;
+        const int base = i * n;
+#pragma unroll 4
+        for (int j = 0; j < n; ++j) {
+            float sy, cy, sz, cz;
+            sincos_f(tb * ys[base + j], sy, cy);
+            const float z = zs[base + j];
+            sincos_f(tc * z, sz, cz);
+            const float zi = small ? z * __builtin_fmaf(tc2 * z, z, 1.0f) : sz * itc;
+            inner = __builtin_fmaf(ws[base + j] * cy, zi, inner);
+        }
+        sum = __builtin_fmaf(cx, inner, sum);
     }
     return sum;
 }
@@ -1062,6 +1105,9 @@ __device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, doub
     } else if constexpr (KIND == kScParacrystal || KIND == kBccParacrystal || KIND == kFccParacrystal) {
         const float r = (float)s[0];
         return a.contrast * k43pi * r * r * r * sph3j_d(q * s[0]);
+    } else if constexpr (KIND == kSuperball) {
+        const float r = (float)s[0];
+        return a.contrast * r * r * r * superball_sum(a, (float)(qa * s[0]), (float)(qb * s[0]), (float)(qc * s[0]));
     } else if constexpr (KIND == kCoreShellParallelepiped) {
         // the core box and the face slabs, each pair 2 cos(Q (edge + t)/2) times one slab
         const float A = (float)s[0], B = (float)s[1], C = (float)s[2];
@@ -1173,6 +1219,8 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
         return (float)kPi * __builtin_fmaf(a.cs_core, core, a.cs_shell * outer);
     } else if constexpr (KIND == kScParacrystal || KIND == kBccParacrystal || KIND == kFccParacrystal) {
         return a.contrast * k43pi * s[0] * s[0] * s[0] * sph3j_f(q * s[0]);
+    } else if constexpr (KIND == kSuperball) {
+        return a.contrast * s[0] * s[0] * s[0] * superball_sum(a, qa * s[0], qb * s[0], qc * s[0]);
     } else if constexpr (KIND == kCoreShellParallelepiped) {
         const float A = s[0], B = s[1], C = s[2];
         const float ta = a.fcsp_t[0], tb = a.fcsp_t[1], tc = a.fcsp_t[2];

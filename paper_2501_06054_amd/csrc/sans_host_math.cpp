@@ -165,6 +165,40 @@ bool sticky_constants(double eta, double tau, int nterms, double* ca, double* cb
     return true;
 }
 
+// Superball |x|^2p + |y|^2p + |z|^2p <= 1: the transform is even in each
+// coordinate, so 8 times the octant's; z is integrated exactly
+// (sin(Q_C zm)/Q_C), x and y by Gauss-Legendre on [0, 1] and [0, ym(x)].
+void superball_rule(double p, int n, float* out)
+{
+    std::vector<double> gx(n), gw(n);
+    gauss_legendre(n, gx.data(), gw.data());
+    const double e = 2.0 * p, ie = 1.0 / e;
+    float* xs = out;
+    float* ys = out + n;
+    float* zs = ys + (size_t)n * n;
+    float* ws = zs + (size_t)n * n;
+    for (int i = 0; i < n; ++i) {
+        const double x = 0.5 * (gx[i] + 1.0);
+        const double xe = std::pow(x, e);
+        const double ym = std::pow(1.0 - xe, ie);
+        xs[i] = (float)x;
+        for (int j = 0; j < n; ++j) {
+            const double y = 0.5 * ym * (gx[j] + 1.0);
+            const double rest = 1.0 - xe - std::pow(y, e);
+            const size_t k = (size_t)i * n + j;
+            ys[k] = (float)y;
+            zs[k] = (float)(rest > 0.0 ? std::pow(rest, ie) : 0.0);
+            ws[k] = (float)(8.0 * 0.5 * gw[i] * 0.5 * ym * gw[j]);
+        }
+    }
+}
+
+double superball_volume(double R, double p)
+{
+    const double g = std::tgamma(1.0 + 0.5 / p);
+    return 8.0 * R * R * R * g * g * g / std::tgamma(1.0 + 1.5 / p);
+}
+
 // E[y^k] of the Schulz distribution: Gamma(a + k) / (Gamma(a) a^k), a = 1/p^2.
 double schulz_moment(double p, int k)
 {
@@ -356,6 +390,8 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
     case 13: case 14: case 15: case 16: case 17: case 18: case 19: case 20: case 21: case 22: case 23:
     case 24: case 29: case 30: case 31: case 32: case 33: case 34: case 35: case 36: case 37: case 40: case 49: case 50:
         return 1.0;  // shape-independent: no particles (the weight uses the cross-section)
+    case 51:
+        return superball_volume(size[0], extra[0]) * size_moment(poly_kind, poly, b0 ? 3 : 0);
     case 12: {
         // the box minus its cavity (monodisperse)
         const double t2 = 2.0 * shell;

@@ -28,6 +28,12 @@ void cap_geometry(bool barbell, double R, double L, double r, double* zc, double
 // The caps' n-point Gauss-Legendre rule at unit size as FP32 arrays [3][n]:
 // t_i in [t0, 1], r sqrt(1 - t_i^2) and 2 pi r^3 (1 - t_i^2) w_i (1 - t0)/2.
 void cap_rule(bool barbell, double R, double L, double r, int n, float* out);
+// The superball's nested n-point Gauss-Legendre rule at unit size, FP32
+// [n + 3 n^2]: x_i in [0, 1]; then per (i, j) y_ij in [0, ym(x_i)], the
+// half-height zm(x_i, y_ij) and the weight 8 (w_i/2)(ym(x_i) w_j/2).
+void superball_rule(double p, int n, float* out);
+inline int superball_rule_size(int n) { return n + 3 * n * n; }
+double superball_volume(double R, double p);
 
 }  // namespace host
 }  // namespace sans

@@ -544,7 +544,8 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 47: batch_tile<47>(a, tl.first, tl.count, hist, tab); break;
         case 48: batch_tile<48>(a, tl.first, tl.count, hist, tab); break;
         case 49: batch_tile<49>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<50>(a, tl.first, tl.count, hist, tab); break;
+        case 50: batch_tile<50>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<51>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -828,6 +829,7 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(48)
         SANS_CASE(49)
         SANS_CASE(50)
+        SANS_CASE(51)
     }
 #undef SANS_CASE
     return nullptr;
@@ -893,6 +895,7 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(48)
         SANS_CASE(49)
         SANS_CASE(50)
+        SANS_CASE(51)
     }
 #undef SANS_CASE
     return nullptr;
@@ -955,6 +958,7 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(48)
         SANS_CASE(49)
         SANS_CASE(50)
+        SANS_CASE(51)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1017,6 +1021,7 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(48)
         SANS_CASE(49)
         SANS_CASE(50)
+        SANS_CASE(51)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1076,6 +1081,7 @@ PqFn pick_pq(int kind)
     case 48: return k_pq_avg<48>;
     case 49: return k_pq_avg<49>;
     case 50: return k_pq_avg<50>;
+    case 51: return k_pq_avg<51>;
     }
     return nullptr;
 }
@@ -1092,7 +1098,7 @@ struct sans_model_s {
     double* d_tab_size = nullptr;
     double* d_tab_norm = nullptr;
     float* d_quad = nullptr;
-    float* d_caps = nullptr;   // end-cap rule [3][quad_n] (barbell, capped cylinder)
+    float* d_caps = nullptr;   // node rule (capped bodies, superball) and structure-factor constants
     double* d_replicas = nullptr;
     size_t replica_pix = 0;
     // tally workspaces (grown on demand, freed with the model)
@@ -1139,14 +1145,58 @@ bool is_sphere_family(int kind)
 bool is_aniso(int kind)
 {
     return (kind >= SANS_CYLINDER && kind <= SANS_HOLLOW_PRISM_THICK && kind != SANS_POLYMER_MICELLE)
-           || (kind >= SANS_ELLIPTICAL_CYLINDER && kind <= SANS_FCC_PARACRYSTAL);
+           || (kind >= SANS_ELLIPTICAL_CYLINDER && kind <= SANS_FCC_PARACRYSTAL) || kind == SANS_SUPERBALL;
+}
+
+// Floats of the per-model node rule in device memory: the end caps' rule
+// [3][quad_n] (barbell, capped cylinder), the superball's nested rule, else 0.
+size_t rule_floats(const sans_params& p)
+{
+    if (p.kind == SANS_BARBELL || p.kind == SANS_CAPPED_CYLINDER) return 3 * (size_t)p.quad_n;
+    if (p.kind == SANS_SUPERBALL) return (size_t)host::superball_rule_size(p.quad_n);
+    return 0;
+}
+
+// The rule, then the constants of an adhesive or square-well structure factor.
+bool needs_sq_coef(const sans_params& p) { return p.sq_phi > 0.0 && p.sq_kind != SANS_SQ_HARD_SPHERE; }
+size_t node_floats(const sans_params& p) { return rule_floats(p) + (needs_sq_coef(p) ? kSqCoef : 0); }
+
+// Fills the node buffer of one parameter set (node_floats(p) floats) and
+// points the kernel arguments at it (base: its device address).
+void fill_nodes(const sans_params& p, float* out, const float* base, TraceArgs& a)
+{
+    const size_t nr = rule_floats(p);
+    if (p.kind == SANS_SUPERBALL) host::superball_rule(p.extra[0], p.quad_n, out);
+    else if (nr) host::cap_rule(p.kind == SANS_BARBELL, p.size[0], p.size[1], p.size[2], p.quad_n, out);
+    if (nr) a.cap_nodes = base;
+    if (!needs_sq_coef(p)) return;
+    float* c = out + nr;
+    for (int k = 0; k < kSqCoef; ++k) c[k] = 0.0f;
+    if (p.sq_kind == SANS_SQ_STICKY_HARD_SPHERE) {
+        double ca[kPySeriesTerms], cb[kPySeriesTerms], hbc[3];
+        host::sticky_constants(p.sq_phi, p.sq_extra[0], kPySeriesTerms, ca, cb, hbc);
+        for (int k = 0; k < kPySeriesTerms; ++k) {
+            c[kSqA + k] = (float)ca[k];
+            c[kSqB + k] = (float)cb[k];
+        }
+        c[kSqE] = (float)(12.0 * p.sq_phi);
+        c[kSqH] = (float)hbc[0];
+        c[kSqBb] = (float)hbc[1];
+        c[kSqC0] = (float)hbc[2];
+    } else {
+        const double w = p.sq_extra[1];
+        c[kSqW8] = (float)(8.0 * p.sq_phi * p.sq_extra[0]);
+        c[kSqW] = (float)w;
+        c[kSqW3] = (float)(w * w * w);
+    }
+    a.sq_coef = base + nr;
 }
 
 int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 50) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 51) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -1164,7 +1214,7 @@ int validate(const sans_params* p)
                            || p->kind == SANS_CORE_SHELL_BICELLE || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL
                            || p->kind == SANS_STACKED_DISKS || p->kind == SANS_SC_PARACRYSTAL
                            || p->kind == SANS_BCC_PARACRYSTAL || p->kind == SANS_FCC_PARACRYSTAL;
-    int nsize = p->kind <= 1 ? 1 : (two_sizes ? 2 : 3);
+    int nsize = (p->kind <= 1 || p->kind == SANS_SUPERBALL) ? 1 : (two_sizes ? 2 : 3);
     if (is_shape_independent(p->kind))
         nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK
                  || p->kind == SANS_TWO_POWER_LAW || p->kind == SANS_SPINODAL || p->kind == SANS_POROD
@@ -1184,6 +1234,15 @@ int validate(const sans_params* p)
         if (p->poly > 0.0 && p->poly_mask != 7)
             return fail(SANS_E_UNSUPPORTED, "barbell / capped cylinder: poly_mask must be 7 (all sizes)");
         if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
+    }
+    if (p->kind == SANS_SUPERBALL) {
+        if (!(p->extra[0] >= 0.25 && p->extra[0] <= 10000.0))
+            return fail(SANS_E_INVALID_ARG, "superball: exponent parameter extra[0] must be in [0.25, 10000]");
+        if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
+        if (p->mode == SANS_MODE_QUAD)
+            return fail(SANS_E_UNSUPPORTED, "superball: no quadrature mode (quad_n^2 nodes per orientation node)");
+        if (p->poly > 0.0 && p->poly_mask != 1)
+            return fail(SANS_E_UNSUPPORTED, "superball: poly_mask must be 1 (one size)");
     }
     if (p->kind == 1 && !(p->shell >= 0.0 && finite(p->shell)))
         return fail(SANS_E_INVALID_ARG, "shell must be >= 0");
@@ -1592,6 +1651,7 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
         a.mic_bc = (float)(p->extra[2] * (p->sld[1] - p->sld[2]));
         a.mic_d = p->extra[3];
     }
+    if (p->kind == SANS_SUPERBALL) a.cap_n = p->quad_n;
     if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
         double zc, t0, vcaps;
         host::cap_geometry(p->kind == SANS_BARBELL, p->size[0], p->size[1], p->size[2], &zc, &t0, &vcaps);
@@ -1633,24 +1693,6 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
         a.sq_2r = (float)(2.0 * p->sq_radius);
         a.sq_24phi = (float)(24.0 * p->sq_phi);
         a.sq_kind = p->sq_kind;
-        if (p->sq_kind == SANS_SQ_STICKY_HARD_SPHERE) {
-            double ca[kPySeriesTerms], cb[kPySeriesTerms], hbc[3];
-            host::sticky_constants(p->sq_phi, p->sq_extra[0], kPySeriesTerms, ca, cb, hbc);
-            for (int k = 0; k < kPySeriesTerms; ++k) {
-                a.sh_ca[k] = (float)ca[k];
-                a.sh_cb[k] = (float)cb[k];
-            }
-            a.sh_e = (float)(12.0 * p->sq_phi);
-            a.sh_h = (float)hbc[0];
-            a.sh_b = (float)hbc[1];
-            a.sh_c0 = (float)hbc[2];
-        }
-        if (p->sq_kind == SANS_SQ_SQUARE_WELL) {
-            const double w = p->sq_extra[1];
-            a.sw_8de = (float)(8.0 * p->sq_phi * p->sq_extra[0]);
-            a.sw_w = (float)w;
-            a.sw_w3 = (float)(w * w * w);
-        }
     }
     a.M = p->table_size;
 }
@@ -1712,15 +1754,15 @@ int configure(sans_model_s* m, const sans_params* p)
         a.tab_norm = m->d_tab_norm;
     }
 
-    // the end caps' rule (every mode)
-    if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
-        std::vector<float> rule(3 * (size_t)p->quad_n);
-        host::cap_rule(p->kind == SANS_BARBELL, p->size[0], p->size[1], p->size[2], p->quad_n, rule.data());
+    // the end caps' rule or the superball's nested rule (every mode), then the
+    // constants of an adhesive or square-well structure factor
+    if (node_floats(*p)) {
+        std::vector<float> rule(node_floats(*p));
         if (m->d_caps) HIP_TRY(hipFree(m->d_caps));
         m->d_caps = nullptr;
         HIP_TRY(hipMalloc(&m->d_caps, sizeof(float) * rule.size()));
+        fill_nodes(*p, rule.data(), m->d_caps, a);
         HIP_TRY(hipMemcpy(m->d_caps, rule.data(), sizeof(float) * rule.size(), hipMemcpyHostToDevice));
-        a.cap_nodes = m->d_caps;
     }
 
     // quadrature nodes: mu in [0, 1], beta in [0, pi/2], size y in
@@ -2372,7 +2414,7 @@ struct BatchCache {
     size_t tables_cap = 0;
     double* d_norm = nullptr;
     int norm_M = 0;
-    float* d_caps = nullptr;   // end-cap rules of the capped bodies, one after another
+    float* d_caps = nullptr;   // node rules and structure-factor constants, one experiment after another
     size_t caps_cap = 0;
     unsigned* d_counter = nullptr;
     hipStream_t cap_stream = nullptr;
@@ -2566,8 +2608,7 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
     std::vector<double> host_tabs;
     std::vector<float> host_caps;
     size_t ncaps = 0;
-    for (int e = 0; e < n_exp; ++e)
-        if (p[e].kind == SANS_BARBELL || p[e].kind == SANS_CAPPED_CYLINDER) ncaps += 3 * (size_t)p[e].quad_n;
+    for (int e = 0; e < n_exp; ++e) ncaps += node_floats(p[e]);
     if ((rc = ensure(c.d_caps, c.caps_cap, std::max<size_t>(1, ncaps)))) return rc;
     if ((rc = ensure(c.d_tables, c.tables_cap, std::max<size_t>(1, ntab * M)))) return rc;
     if ((rc = ensure(c.d_jobs, c.jobs_cap, std::max<size_t>(1, ntab)))) return rc;
@@ -2600,12 +2641,10 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
             jobs.push_back(schulz_job(p[e].poly, (unsigned long long)(jobs.size() * (size_t)M)));
         }
         if (is_aniso(p[e].kind) && p[e].orient_kind == SANS_ORIENT_GAUSSIAN) exps[e].tab_norm = c.d_norm;
-        if (p[e].kind == SANS_BARBELL || p[e].kind == SANS_CAPPED_CYLINDER) {
+        if (node_floats(p[e])) {
             const size_t off = host_caps.size();
-            host_caps.resize(off + 3 * (size_t)p[e].quad_n);
-            host::cap_rule(p[e].kind == SANS_BARBELL, p[e].size[0], p[e].size[1], p[e].size[2], p[e].quad_n,
-                           host_caps.data() + off);
-            exps[e].cap_nodes = c.d_caps + off;
+            host_caps.resize(off + node_floats(p[e]));
+            fill_nodes(p[e], host_caps.data() + off, c.d_caps + off, exps[e]);
         }
     }
     if (!host_caps.empty())

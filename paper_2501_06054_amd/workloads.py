@@ -32,7 +32,7 @@ EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle", "hollow_
                "vesicle", "multilayer_vesicle", "linear_pearls", "fractal", "fractal_core_shell",
                "elliptical_cylinder", "core_shell_bicelle", "core_shell_parallelepiped",
                "core_shell_bicelle_elliptical", "stacked_disks", "sc_paracrystal", "bcc_paracrystal",
-               "fcc_paracrystal")
+               "fcc_paracrystal", "superball")
 #: shape-independent models: a cross-section in 1/cm, extra[0] = I(0)
 SHAPE_INDEPENDENT_KINDS = ("guinier", "ornstein_zernike", "dab", "gauss_coil", "poly_gauss_coil",
                            "teubner_strey", "power_law", "gaussian_peak", "lorentz_peak", "mass_fractal",
@@ -318,6 +318,18 @@ def mass_surface_fractal() -> dict:
                               nx=256, ny=256))
 
 
+def oriented_superball() -> dict:
+    """Superballs of half-edge 40 A and exponent parameter 2.5 (a rounded
+    cube), axes tilted 30/20/10 deg with Gaussian spread 10 deg, their
+    transform by a 24 x 24 Gauss-Legendre rule per event, 256x256, 1e8
+    neutrons."""
+    return dict(name="oriented_superball", n=10**8, seed=26, exp_id=0,
+                params=params(kind="superball", size=(40.0, 0.0, 0.0), sld=(1e-6, 0, 0), extra=(2.5, 0, 0, 0),
+                              quad_n=24, phi=0.01, orient_kind="gaussian",
+                              orient_mean=(30 * DEG, 20 * DEG, 10 * DEG),
+                              orient_sigma=(10 * DEG, 10 * DEG, 10 * DEG), nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -343,6 +355,7 @@ WORKLOADS = {
     "oriented_fcc_paracrystal": oriented_fcc_paracrystal,
     "sticky_coreshell": sticky_coreshell,
     "mass_surface_fractal": mass_surface_fractal,
+    "oriented_superball": oriented_superball,
 }
 
 

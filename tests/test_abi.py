@@ -163,6 +163,12 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
     # a deep, wide well drives 1/S(0) below zero
     (dict(kind="sphere", sq_phi=0.2, sq_radius=50.0, sq_kind="square_well", sq_extra=(3.0, 2.0)),
      "SANS_E_DOMAIN"),
+    (dict(kind="superball", size=(30.0, 0.0, 0.0), extra=(0.2, 0, 0, 0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="superball", size=(30.0, 0.0, 0.0), extra=(2.0, 0, 0, 0), quad_n=0), "SANS_E_INVALID_ARG"),
+    (dict(kind="superball", size=(30.0, 0.0, 0.0), extra=(2.0, 0, 0, 0), mode="quad", orient_kind="isotropic"),
+     "SANS_E_UNSUPPORTED"),
+    (dict(kind="superball", size=(30.0, 0.0, 0.0), extra=(2.0, 0, 0, 0), poly=0.1, poly_mask=3),
+     "SANS_E_UNSUPPORTED"),
 ])
 def test_capped_body_params_rejected_without_gpu(S, over, code):
     from paper_2501_06054_amd import workloads as W
@@ -174,7 +180,7 @@ def test_capped_body_params_rejected_without_gpu(S, over, code):
 def test_unknown_kind_rejected_without_gpu(S):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=1.0))
-    sp.kind = 51
+    sp.kind = 52
     h = C.c_void_p()
     assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED
 

@@ -69,7 +69,7 @@ def check_detector(d_gpu, d_orc, where="", count=None, w_max=None):
 
 
 # models judged pixel by pixel with the summed per-neutron bar
-SUMMED_BAR = ("barbell", "capped_cylinder", "hollow_prism")
+SUMMED_BAR = ("barbell", "capped_cylinder", "hollow_prism", "superball")
 
 
 def oracle_detector(p, n, seed, first=0):
@@ -300,6 +300,14 @@ PER_NEUTRON = {
     "repulsive_shoulder_cylinder": (W.params(kind="cylinder", size=(20.0, 120.0, 0), orient_kind="isotropic",
                                              sq_phi=0.2, sq_radius=35.0, sq_kind="square_well",
                                              sq_extra=(-0.8, 1.6)), 30011),
+    # superball: a 2-D Gauss-Legendre rule per event
+    "oriented_superball": (W.workload("oriented_superball")["params"], 20021),
+    "superball_iso_poly": (W.params(kind="superball", size=(30.0, 0, 0), extra=(1.5, 0, 0, 0), quad_n=20,
+                                    orient_kind="isotropic", poly=0.1, poly_mask=1), 10011),
+    "superball_octahedron": (W.params(kind="superball", size=(50.0, 0, 0), extra=(0.5, 0, 0, 0), quad_n=30,
+                                      orient_mean=(0.4, 0.9, 0.3)), 10011),
+    "superball_cubic_small_q": (W.params(kind="superball", size=(8.0, 0, 0), extra=(40.0, 0, 0, 0), quad_n=7,
+                                         orient_kind="uniform_angles"), 10011),
 }
 
 
@@ -329,7 +337,8 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "star_polymer", "gaussian_peak", "multilayer_vesicle", "linear_pearls_poly", "spinodal",
              "fractal_poly", "polymer_excl_volume", "broad_peak", "oriented_elliptical_cylinder",
              "bicelle_poly_iso", "cs_parallelepiped_gauss", "stacked_disks_gauss", "oriented_fcc_paracrystal",
-             "mass_surface_fractal", "gel_fit", "sticky_coreshell", "square_well_poly_sphere"]
+             "mass_surface_fractal", "gel_fit", "sticky_coreshell", "square_well_poly_sphere",
+             "oriented_superball"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
