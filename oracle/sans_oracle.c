@@ -71,7 +71,11 @@ typedef struct {
                               paracrystals of spheres; shape-independent:
                               49 mass-surface fractal, 50 gel (fractal
                               network plus frozen inhomogeneities);
-                              oriented: 51 superball                        */
+                              oriented: 51 superball; randomly oriented
+                              lamellae: 52 bilayers with head and tail
+                              groups, 53 stacks with Caille fluctuations,
+                              54 head-tail bilayers in Caille stacks, 55
+                              paracrystalline stacks                         */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -964,12 +968,65 @@ static double sphere_family_f2(const orc_params* p, const double s[3], double q)
     return 0.0;
 }
 
+/* Randomly oriented lamellae (Tables I-II, group C).  A flat sheet of area
+ * A with the transverse contrast profile drho(z) scatters
+ * |F1(Q_z)|^2 |S_A(Q_par)|^2; averaged over the directions of its normal,
+ * the in-plane factor, whose integral over Q_par is (2 pi)^2 A, is picked up
+ * at the two poles, giving 2 pi A |F1(q)|^2 / q^2.  Sheets of thickness
+ * delta at volume fraction phi have phi/delta of area per volume, so
+ *   dSigma/dOmega = phi (2 pi / delta) |F1(q)|^2 S(q) / q^2,
+ * S the stacking factor per sheet (1 for isolated sheets).  Profiles are
+ * symmetric: F1(q) = int drho(z) cos(q z) dz.  Here f2 is returned per unit
+ * phi (the weight's phi / <V> with <V> = 1). */
+static int lamellar(int kind) { return kind >= 52 && kind <= 55; }
+
+/* Caille stacking of N sheets, repeat distance d, Caille parameter eta: the
+ * mean-square displacement of sheets n apart grows as (eta d^2 / 2 pi^2)
+ * (ln(pi n) + gamma), so S = 1 + 2 sum_{n<N} (1 - n/N) cos(q d n)
+ * exp(-eta (q d / 2 pi)^2 (ln(pi n) + gamma)). */
+static double caille_sq(double q, double d, int n, double eta)
+{
+    const double euler_gamma = 0.57721566490153286061;
+    double a = eta * (q * d / (2.0 * ORC_PI)) * (q * d / (2.0 * ORC_PI)), st = 1.0;
+    for (int k = 1; k < n; ++k)
+        st += 2.0 * (1.0 - (double)k / n) * cos(q * d * k) * exp(-a * (log(ORC_PI * k) + euler_gamma));
+    return st;
+}
+
+static double lamellar_iq(const orc_params* p, const double s[3], double q)
+{
+    double rt = p->sld[0] - p->sld[2], rh = p->sld[1] - p->sld[2];
+    double f1, delta, st = 1.0;
+    if (p->kind == 52 || p->kind == 54) {
+        /* tails over |z| < L_T (sld[0]), heads over L_T < |z| < L_T + L_H (sld[1]) */
+        double lt = s[0], lh = s[1];
+        delta = 2.0 * (lt + lh);
+        f1 = 2.0 * ((rt - rh) * sin(q * lt) + rh * sin(q * (lt + lh))) / q;
+    } else {
+        /* one slab of thickness delta = size[0] (sld[0]) */
+        delta = s[0];
+        f1 = 2.0 * rt * sin(0.5 * q * delta) / q;
+    }
+    int n = (int)p->extra[0];
+    if (p->kind == 53) st = caille_sq(q, s[1], n, p->extra[1]);
+    if (p->kind == 54) st = caille_sq(q, s[2], n, p->extra[1]);
+    if (p->kind == 55) {
+        /* paracrystal: spacings independent Gaussians (mean d = size[1], width
+           extra[1]), so sheets n apart are n d +- sqrt(n) sigma */
+        double d = s[1], sg = p->extra[1];
+        for (int k = 1; k < n; ++k)
+            st += 2.0 * (1.0 - (double)k / n) * cos(q * d * k) * exp(-0.5 * k * q * q * sg * sg);
+    }
+    return 2.0 * ORC_PI / delta * f1 * f1 * st / (q * q);
+}
+
 /* The squared amplitude of one particle, or for the micelle its scattering
  * per particle (it has incoherent chain terms); for the shape-independent
  * models their cross-section in 1/cm. */
 static double form_f2(const orc_params* p, const double s[3], double q, double qa, double qb, double qc)
 {
     if (shape_independent(p->kind)) return shape_independent_iq(p, s, q);
+    if (lamellar(p->kind)) return lamellar_iq(p, s, q);
     if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
     if (p->kind >= 25 && p->kind <= 28) return sphere_family_f2(p, s, q);
     if (p->kind == 45) {
@@ -1116,6 +1173,8 @@ double orc_mean_volume(const orc_params* p)
              * size_moment(p, p->poly_mask == 7 ? 3 : 0);
     case 51:
         return superball_volume(s[0], p->extra[0]) * size_moment(p, b0 ? 3 : 0);
+    case 52: case 53: case 54: case 55: /* lamellae: f2 is per unit volume fraction */
+        return 1.0;
     case 25: /* fuzzy sphere: the sphere's volume */
         return vol_sphere(s[0]) * size_moment(p, b0 ? 3 : 0);
     case 26: { /* vesicle: the shell, 4/3 pi ((R y + t)^3 - (R y)^3) */

@@ -1567,3 +1567,99 @@ def test_superball_mean_volume(orc):
     z = 1 / 0.2 ** 2
     y3 = (z + 1) * (z + 2) / z ** 2     # <y^3> of the Schulz distribution of mean 1
     assert orc.mean_volume(p) == pytest.approx(8 * 30.0 ** 3 * g ** 3 / math.gamma(1 + 3 / 4.0) * y3, rel=1e-12)
+
+
+# ---------------------------------------------------------------- lamellae
+
+def _lam(orc, q, **over):
+    p = W.params(**over)
+    return orc.form_f2(p, q, (0.0, 0.0, q))
+
+
+def _laue(q, d, n):
+    x = 0.5 * q * d
+    return math.sin(n * x) ** 2 / (n * math.sin(x) ** 2)
+
+
+@pytest.mark.parametrize("q", [0.003, 0.02, 0.07])
+def test_lamellar_head_tail_profile_transform(orc, q):
+    """The bilayer's transverse transform against a quadrature of its
+    profile (tails |z| < L_T, heads out to L_T + L_H), and the slab's closed
+    form when heads and tails match; the sheets' 2 pi / (delta q^2)."""
+    from scipy import integrate
+    lt, lh = 14.0, 8.0
+    rt, rh, rs = -0.4e-6, 3.0e-6, 6.3e-6
+    prof = lambda z: (rt if abs(z) < lt else rh) - rs
+    f1 = 0.0
+    for a, b in ((-lt - lh, -lt), (-lt, lt), (lt, lt + lh)):
+        v, _ = integrate.quad(lambda z: prof(z) * math.cos(q * z), a, b, epsabs=0, epsrel=1e-13)
+        f1 += v
+    delta = 2 * (lt + lh)
+    got = _lam(orc, q, kind="lamellar_hg", size=(lt, lh, 0.0), sld=(rt, rh, rs))
+    assert got == pytest.approx(2 * math.pi / delta * f1 ** 2 / q ** 2, rel=1e-11)
+    same = _lam(orc, q, kind="lamellar_hg", size=(lt, lh, 0.0), sld=(rh, rh, rs))
+    slab = (rh - rs) * delta * math.sin(0.5 * q * delta) / (0.5 * q * delta)
+    assert same == pytest.approx(2 * math.pi / delta * slab ** 2 / q ** 2, rel=1e-12)
+    one = _lam(orc, q, kind="lamellar_stack_caille", size=(delta, 60.0, 0.0), sld=(rh, 0.0, rs),
+               extra=(1.0, 0.1, 0.0, 0.0))
+    assert one == pytest.approx(same, rel=1e-13)
+
+
+@pytest.mark.parametrize("q", [0.02, 0.05])
+def test_sheet_orientation_average_is_two_pi_area_over_q2(q):
+    """The isotropic average of a large thin disc's in-plane factor,
+    (1/2) int |pi R^2 2J1(q R sin t)/(q R sin t)|^2 sin t dt, tends to
+    2 pi (pi R^2) / q^2 (the factor the lamellar cross-section carries)."""
+    from scipy import integrate, special
+    R = 4000.0
+    area = math.pi * R * R
+    def f(t):
+        x = q * R * math.sin(t)
+        lam = 1.0 if x < 1e-12 else 2 * special.j1(x) / x
+        return (area * lam) ** 2 * math.sin(t)
+    pts = [k / (q * R) for k in range(1, 200, 5)]
+    v, _ = integrate.quad(f, 0.0, 0.5 * math.pi, points=pts, limit=4000, epsabs=0, epsrel=1e-10)
+    assert v == pytest.approx(2 * math.pi * area / q ** 2, rel=3.0 / (q * R))
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 30])
+def test_lamellar_stacks_without_disorder_are_laue(orc, n):
+    """Without fluctuations (Caille eta = 0) or spacing disorder (sigma = 0)
+    the stacking factor is the Laue function sin^2(N q d/2)/(N sin^2(q d/2))."""
+    d, delta = 63.0, 30.0
+    for q in (0.004, 0.031, 0.0997):
+        slab = _lam(orc, q, kind="lamellar_stack_caille", size=(delta, d, 0.0), extra=(1.0, 0.0, 0, 0))
+        c = _lam(orc, q, kind="lamellar_stack_caille", size=(delta, d, 0.0), extra=(float(n), 0.0, 0, 0))
+        pc = _lam(orc, q, kind="lamellar_stack_paracrystal", size=(delta, d, 0.0), extra=(float(n), 0.0, 0, 0))
+        assert c == pytest.approx(slab * _laue(q, d, n), rel=1e-9)
+        assert pc == pytest.approx(slab * _laue(q, d, n), rel=1e-9)
+
+
+def test_lamellar_paracrystal_tends_to_the_infinite_paracrystal(orc):
+    """Many sheets with independent Gaussian spacings: (1 - e^2)/(1 - 2 e
+    cos(q d) + e^2), e = exp(-(q sigma)^2 / 2), up to O(1/N)."""
+    d, sg, delta = 70.0, 20.0, 30.0
+    for q in (0.03, 0.05, 0.09):
+        slab = _lam(orc, q, kind="lamellar_stack_caille", size=(delta, d, 0.0), extra=(1.0, 0.0, 0, 0))
+        st = _lam(orc, q, kind="lamellar_stack_paracrystal", size=(delta, d, 0.0),
+                  extra=(20000.0, sg, 0, 0)) / slab
+        e = math.exp(-0.5 * (q * sg) ** 2)
+        assert st == pytest.approx((1 - e * e) / (1 - 2 * e * math.cos(q * d) + e * e), rel=2e-3)
+
+
+def test_caille_damps_the_higher_orders_more(orc):
+    """Caille fluctuations lower the Bragg peaks, more at higher order (the
+    exponent grows as (q d)^2): the peak ratio to the ideal stack falls with
+    the order."""
+    d, delta, n = 60.0, 25.0, 20
+    ratios = []
+    for m in (1, 2, 3):
+        q = 2 * math.pi * m / d
+        ideal = _lam(orc, q, kind="lamellar_stack_caille", size=(delta, d, 0.0), extra=(float(n), 0.0, 0, 0))
+        fl = _lam(orc, q, kind="lamellar_stack_caille", size=(delta, d, 0.0), extra=(float(n), 0.1, 0, 0))
+        ratios.append(fl / ideal)
+    assert 1 > ratios[0] > ratios[1] > ratios[2] > 0
+    # at the first order: 1 + 2 sum (1 - k/N) (pi k)^(-eta) e^(-eta gamma), over N
+    g = 0.57721566490153286061
+    want = (1 + 2 * sum((1 - k / n) * (math.pi * k) ** (-0.1) * math.exp(-0.1 * g) for k in range(1, n))) / n
+    assert ratios[0] == pytest.approx(want, rel=1e-10)
