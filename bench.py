@@ -89,6 +89,8 @@ STEP = {
     "msf_I":         ((8,   0,  0,  3, 3, 0), 10),  # mass-surface fractal: two log2, one exp2
     "sb_row":        ((16,  3,  0,  0, 0, 0), 22),  # superball, per x node: cos(Q_A R x), the row's sum
     "sb_node":       ((32,  6,  0,  0, 0, 0), 44),  # superball, per (x, y) node: cos(Q_B R y), sin(Q_C R zm)/Q_C R
+    "lam_hg_F":      ((24,  0,  0,  4, 0, 1), 30),  # head-tail bilayer: two sinc (FP64 phases), 2 pi/delta, 1/q^2
+    "caille_term":   ((18,  3,  0,  6, 1, 0), 24),  # one sheet pair of a Caille stack: FP64 phase reduction, cos, exp
     "weight":        ((3,   0,  0,  2, 0, 0), 3),   # A11
     "detector":      ((0,   5,  0, 23, 0, 1), 0),   # A12: plane crossing (quotient), pixel
     "tally":         ((0,   2,  0,  0, 0, 0), 0),   # A13: address; the add itself is a memory op
@@ -137,6 +139,8 @@ PATHS = {
     # superball: the 24 x 24 rule of the workload
     "oriented_superball": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
                           + ["qvec"] + ["orient_angle"] * 3 + ["project_abc"] + ["sb_row"] * 24 + ["sb_node"] * 576,
+    # lamellae: 30 sheets, 29 pair terms
+    "lamellar_caille": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["lam_hg_F"] + ["caille_term"] * 29,
 }
 # Exact-average paths, per quadrature node (76 x 76 = 5776 nodes per neutron),
 # all FP32:

@@ -191,7 +191,25 @@ typedef enum {
      * Its transform is integrated over x and y by quad_n-point Gauss-Legendre
      * rules (quad_n^2 nodes per event, in every mode), over z exactly;
      * SANS_MODE_QUAD is not provided (quad_n^2 nodes per orientation node). */
-    SANS_SUPERBALL = 51
+    SANS_SUPERBALL = 51,
+    /* Randomly oriented lamellae (Tables I-II, group C): flat sheets at
+     * volume fraction phi, the weight phi (2 pi / delta) F1(q)^2 S(q) / q^2
+     * with F1 the transform of the sheet's transverse contrast profile and
+     * S the stacking factor of extra[0] (integer, 1..1000) sheets;
+     * monodisperse, no structure factor (poly > 0 or sq_phi > 0 is
+     * SANS_E_UNSUPPORTED). */
+    SANS_LAMELLAR_HG = 52,       /* bilayer: tails (sld[0]) over |z| < size[0],
+                                    heads (sld[1]) out to size[0] + size[1];
+                                    delta = 2 (size[0] + size[1]); S = 1    */
+    SANS_LAMELLAR_STACK_CAILLE = 53, /* slabs of thickness size[0] (sld[0]),
+                                    repeat distance size[1], Caille parameter
+                                    extra[1] in [0, 1]                        */
+    SANS_LAMELLAR_HG_STACK_CAILLE = 54, /* head-tail bilayers (size[0],
+                                    size[1], as SANS_LAMELLAR_HG) in a Caille
+                                    stack of repeat distance size[2]          */
+    SANS_LAMELLAR_STACK_PARACRYSTAL = 55 /* slabs of thickness size[0], spacings
+                                    Gaussian of mean size[1] and width
+                                    extra[1] >= 0 (A)                         */
 } sans_kind;
 
 /* Structure factor S(q) of the particles (when sq_phi > 0): volume fraction

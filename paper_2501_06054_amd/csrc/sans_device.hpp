@@ -140,6 +140,10 @@ struct TraceArgs {
     // elliptical bicelle: cross-section ratio; stacked disks: spacing d, spread
     // sigma, count (sf_n); paracrystals: primitive vectors (A), (g D)^2 / 2
     double bi_x, sd_d, sd_sig, pc_v[3][3], pc_b;
+    // lamellae: 2 pi / delta and the Caille parameter (the repeat distance,
+    // spacing spread and count in sd_d, sd_sig, sf_n; the Caille exponents'
+    // gamma + ln(pi n) in cap_nodes)
+    float lam_c, lam_eta;
     // run
     uint64_t first, n;
     uint32_t seed_lo, seed_hi, exp_id;
@@ -559,7 +563,12 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kFractalCoreShell = 39, kPolymerExclVolume = 40, kEllipticalCylinder = 41,
               kCoreShellBicelle = 42, kCoreShellParallelepiped = 43, kCoreShellBicelleElliptical = 44,
               kStackedDisks = 45, kScParacrystal = 46, kBccParacrystal = 47, kFccParacrystal = 48,
-              kMassSurfaceFractal = 49, kGelFit = 50, kSuperball = 51 };
+              kMassSurfaceFractal = 49, kGelFit = 50, kSuperball = 51, kLamellarHg = 52,
+              kLamellarStackCaille = 53, kLamellarHgStackCaille = 54, kLamellarStackParacrystal = 55 };
+
+// Randomly oriented lamellae: the weight per unit volume fraction.
+template <int KIND>
+constexpr bool kLamellar = KIND >= kLamellarHg && KIND <= kLamellarStackParacrystal;
 
 // F^2 multiplied by an orientation-dependent interference factor (stacked
 // disks, paracrystals).
@@ -891,6 +900,54 @@ __device__ __forceinline__ float shape_iq(const TraceArgs& a, double len, double
         }
         return a.si_scale * (float)(v / a.si_b);
     }
+}
+
+// Randomly oriented lamellae (Tables I-II, group C), per unit volume fraction:
+// (2 pi / delta) F1(q)^2 S(q) / q^2 with the sheet's transverse transform F1
+// (head-tail bilayer: tails |z| < L_T, heads out to L_T + L_H; else one slab of
+// thickness delta) and the stacking factor S of N sheets: Caille,
+// 1 + 2 sum_n (1 - n/N) cos(q d n) exp(-eta (q d/2 pi)^2 (gamma + ln(pi n))),
+// or a paracrystal with independent Gaussian spacings,
+// 1 + 2 sum_n (1 - n/N) cos(q d n) exp(-n (q sigma)^2 / 2); phases in FP64.
+template <int KIND>
+__device__ __forceinline__ float lamellar_f2(const TraceArgs& a, double q)
+{
+    float f1;
+    if constexpr (KIND == kLamellarHg || KIND == kLamellarHgStackCaille) {
+        const double lt = a.size[0], lo = a.size[0] + a.size[1];
+        f1 = 2.0f * __builtin_fmaf(a.cs_core * (float)lt, sinc_d(q * lt), a.cs_shell * (float)lo * sinc_d(q * lo));
+    } else {
+        f1 = a.contrast * (float)a.size[0] * sinc_d(0.5 * q * a.size[0]);
+    }
+    float st = 1.0f;
+    if constexpr (KIND != kLamellarHg) {
+        const int n = a.sf_n;
+        const float inv_n = 1.0f / (float)n;
+        const double qd = q * a.sd_d;
+        float s = 0.0f;
+        if constexpr (KIND == kLamellarStackParacrystal) {
+            const float damp = (float)exp(-0.5 * q * q * a.sd_sig * a.sd_sig);
+            float dk = 1.0f;
+            for (int k = 1; k < n; ++k) {
+                float sv, cv;
+                sincos_phase(qd * k, sv, cv);
+                dk *= damp;
+                s = __builtin_fmaf(__builtin_fmaf(-(float)k, inv_n, 1.0f) * dk, cv, s);
+            }
+        } else {
+            const float x = (float)(qd * (0.5 / kPi));
+            const float al = -a.lam_eta * x * x;
+            const float* __restrict__ ln = a.cap_nodes;
+            for (int k = 1; k < n; ++k) {
+                float sv, cv;
+                sincos_phase(qd * k, sv, cv);
+                s = __builtin_fmaf(__builtin_fmaf(-(float)k, inv_n, 1.0f) * __expf(al * ln[k]), cv, s);
+            }
+        }
+        st = __builtin_fmaf(2.0f, s, 1.0f);
+    }
+    const float iq = (float)(1.0 / q);
+    return a.lam_c * f1 * f1 * st * iq * iq;
 }
 
 // Isotropic sphere-based particles (Tables I-II, group F), F^2 averaged over
@@ -1285,6 +1342,8 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
                 f2 = micelle_f2(a, s[0], s[1], (double)q);
             } else if constexpr (kShapeIndependent<KIND>) {
                 f2 = shape_iq<KIND>(a, a.size[0], (double)q);
+            } else if constexpr (kLamellar<KIND>) {
+                f2 = lamellar_f2<KIND>(a, (double)q);
             } else if constexpr (kSphereFamily<KIND>) {
                 f2 = sphere_family_f2<KIND>(a, s[0], (double)q);
             } else {
@@ -1536,6 +1595,8 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
                             (a.poly_mask & 2) ? a.size[1] * y : a.size[1], qd);
         } else if constexpr (kShapeIndependent<KIND>) {
             f2 = shape_iq<KIND>(a, a.size[0], qd);
+        } else if constexpr (kLamellar<KIND>) {
+            f2 = lamellar_f2<KIND>(a, qd);
         } else if constexpr (kSphereFamily<KIND>) {
             f2 = sphere_family_f2<KIND>(a, (a.poly_mask & 1) ? a.size[0] * y : a.size[0], qd);
         } else {

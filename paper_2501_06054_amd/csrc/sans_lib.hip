@@ -545,7 +545,11 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 48: batch_tile<48>(a, tl.first, tl.count, hist, tab); break;
         case 49: batch_tile<49>(a, tl.first, tl.count, hist, tab); break;
         case 50: batch_tile<50>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<51>(a, tl.first, tl.count, hist, tab); break;
+        case 51: batch_tile<51>(a, tl.first, tl.count, hist, tab); break;
+        case 52: batch_tile<52>(a, tl.first, tl.count, hist, tab); break;
+        case 53: batch_tile<53>(a, tl.first, tl.count, hist, tab); break;
+        case 54: batch_tile<54>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<55>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -830,6 +834,10 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(49)
         SANS_CASE(50)
         SANS_CASE(51)
+        SANS_CASE(52)
+        SANS_CASE(53)
+        SANS_CASE(54)
+        SANS_CASE(55)
     }
 #undef SANS_CASE
     return nullptr;
@@ -896,6 +904,10 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(49)
         SANS_CASE(50)
         SANS_CASE(51)
+        SANS_CASE(52)
+        SANS_CASE(53)
+        SANS_CASE(54)
+        SANS_CASE(55)
     }
 #undef SANS_CASE
     return nullptr;
@@ -959,6 +971,10 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(49)
         SANS_CASE(50)
         SANS_CASE(51)
+        SANS_CASE(52)
+        SANS_CASE(53)
+        SANS_CASE(54)
+        SANS_CASE(55)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1022,6 +1038,10 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(49)
         SANS_CASE(50)
         SANS_CASE(51)
+        SANS_CASE(52)
+        SANS_CASE(53)
+        SANS_CASE(54)
+        SANS_CASE(55)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1082,6 +1102,10 @@ PqFn pick_pq(int kind)
     case 49: return k_pq_avg<49>;
     case 50: return k_pq_avg<50>;
     case 51: return k_pq_avg<51>;
+    case 52: return k_pq_avg<52>;
+    case 53: return k_pq_avg<53>;
+    case 54: return k_pq_avg<54>;
+    case 55: return k_pq_avg<55>;
     }
     return nullptr;
 }
@@ -1154,6 +1178,7 @@ size_t rule_floats(const sans_params& p)
 {
     if (p.kind == SANS_BARBELL || p.kind == SANS_CAPPED_CYLINDER) return 3 * (size_t)p.quad_n;
     if (p.kind == SANS_SUPERBALL) return (size_t)host::superball_rule_size(p.quad_n);
+    if (p.kind == SANS_LAMELLAR_STACK_CAILLE || p.kind == SANS_LAMELLAR_HG_STACK_CAILLE) return (size_t)p.extra[0];
     return 0;
 }
 
@@ -1166,8 +1191,16 @@ size_t node_floats(const sans_params& p) { return rule_floats(p) + (needs_sq_coe
 void fill_nodes(const sans_params& p, float* out, const float* base, TraceArgs& a)
 {
     const size_t nr = rule_floats(p);
-    if (p.kind == SANS_SUPERBALL) host::superball_rule(p.extra[0], p.quad_n, out);
-    else if (nr) host::cap_rule(p.kind == SANS_BARBELL, p.size[0], p.size[1], p.size[2], p.quad_n, out);
+    if (p.kind == SANS_SUPERBALL) {
+        host::superball_rule(p.extra[0], p.quad_n, out);
+    } else if (p.kind == SANS_LAMELLAR_STACK_CAILLE || p.kind == SANS_LAMELLAR_HG_STACK_CAILLE) {
+        // the Caille exponents' gamma + ln(pi n), n = 0 .. N - 1 (n = 0 unused)
+        const double euler_gamma = 0.57721566490153286061;
+        out[0] = 0.0f;
+        for (size_t k = 1; k < nr; ++k) out[k] = (float)(euler_gamma + std::log(kPi * (double)k));
+    } else if (nr) {
+        host::cap_rule(p.kind == SANS_BARBELL, p.size[0], p.size[1], p.size[2], p.quad_n, out);
+    }
     if (nr) a.cap_nodes = base;
     if (!needs_sq_coef(p)) return;
     float* c = out + nr;
@@ -1196,7 +1229,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 51) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 55) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -1213,7 +1246,9 @@ int validate(const sans_params* p)
                            || p->kind == SANS_HOLLOW_CYLINDER || p->kind == SANS_CORE_SHELL_CYLINDER
                            || p->kind == SANS_CORE_SHELL_BICELLE || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL
                            || p->kind == SANS_STACKED_DISKS || p->kind == SANS_SC_PARACRYSTAL
-                           || p->kind == SANS_BCC_PARACRYSTAL || p->kind == SANS_FCC_PARACRYSTAL;
+                           || p->kind == SANS_BCC_PARACRYSTAL || p->kind == SANS_FCC_PARACRYSTAL
+                           || p->kind == SANS_LAMELLAR_HG || p->kind == SANS_LAMELLAR_STACK_CAILLE
+                           || p->kind == SANS_LAMELLAR_STACK_PARACRYSTAL;
     int nsize = (p->kind <= 1 || p->kind == SANS_SUPERBALL) ? 1 : (two_sizes ? 2 : 3);
     if (is_shape_independent(p->kind))
         nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK
@@ -1234,6 +1269,18 @@ int validate(const sans_params* p)
         if (p->poly > 0.0 && p->poly_mask != 7)
             return fail(SANS_E_UNSUPPORTED, "barbell / capped cylinder: poly_mask must be 7 (all sizes)");
         if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
+    }
+    if (p->kind >= SANS_LAMELLAR_HG && p->kind <= SANS_LAMELLAR_STACK_PARACRYSTAL) {
+        if (p->kind != SANS_LAMELLAR_HG
+            && !(p->extra[0] >= 1.0 && p->extra[0] <= 1000.0 && p->extra[0] == std::floor(p->extra[0])))
+            return fail(SANS_E_INVALID_ARG, "lamellar stack: integer sheet count extra[0] in 1..1000");
+        if ((p->kind == SANS_LAMELLAR_STACK_CAILLE || p->kind == SANS_LAMELLAR_HG_STACK_CAILLE)
+            && !(p->extra[1] >= 0.0 && p->extra[1] <= 1.0))
+            return fail(SANS_E_INVALID_ARG, "Caille stack: Caille parameter extra[1] must be in [0, 1]");
+        if (p->kind == SANS_LAMELLAR_STACK_PARACRYSTAL && !(p->extra[1] >= 0.0 && finite(p->extra[1])))
+            return fail(SANS_E_INVALID_ARG, "paracrystalline stack: spacing spread extra[1] must be >= 0");
+        if (p->poly > 0.0) return fail(SANS_E_UNSUPPORTED, "lamellae: monodisperse only");
+        if (p->sq_phi > 0.0) return fail(SANS_E_UNSUPPORTED, "lamellae: no structure factor");
     }
     if (p->kind == SANS_SUPERBALL) {
         if (!(p->extra[0] >= 0.25 && p->extra[0] <= 10000.0))
@@ -1652,6 +1699,15 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
         a.mic_d = p->extra[3];
     }
     if (p->kind == SANS_SUPERBALL) a.cap_n = p->quad_n;
+    if (p->kind >= SANS_LAMELLAR_HG && p->kind <= SANS_LAMELLAR_STACK_PARACRYSTAL) {
+        const bool hg = p->kind == SANS_LAMELLAR_HG || p->kind == SANS_LAMELLAR_HG_STACK_CAILLE;
+        const double delta = hg ? 2.0 * (p->size[0] + p->size[1]) : p->size[0];
+        a.lam_c = (float)(2.0 * kPi / delta);
+        a.lam_eta = (float)p->extra[1];
+        a.sf_n = p->kind == SANS_LAMELLAR_HG ? 1 : (int)p->extra[0];
+        a.sd_d = p->kind == SANS_LAMELLAR_HG_STACK_CAILLE ? p->size[2] : p->size[1];
+        a.sd_sig = p->kind == SANS_LAMELLAR_STACK_PARACRYSTAL ? p->extra[1] : 0.0;
+    }
     if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
         double zc, t0, vcaps;
         host::cap_geometry(p->kind == SANS_BARBELL, p->size[0], p->size[1], p->size[2], &zc, &t0, &vcaps);

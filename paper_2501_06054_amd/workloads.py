@@ -33,6 +33,8 @@ EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle", "hollow_
                "elliptical_cylinder", "core_shell_bicelle", "core_shell_parallelepiped",
                "core_shell_bicelle_elliptical", "stacked_disks", "sc_paracrystal", "bcc_paracrystal",
                "fcc_paracrystal", "superball")
+#: randomly oriented lamellae (weight per unit volume fraction phi)
+LAMELLAR_KINDS = ("lamellar_hg", "lamellar_stack_caille", "lamellar_hg_stack_caille", "lamellar_stack_paracrystal")
 #: shape-independent models: a cross-section in 1/cm, extra[0] = I(0)
 SHAPE_INDEPENDENT_KINDS = ("guinier", "ornstein_zernike", "dab", "gauss_coil", "poly_gauss_coil",
                            "teubner_strey", "power_law", "gaussian_peak", "lorentz_peak", "mass_fractal",
@@ -330,6 +332,16 @@ def oriented_superball() -> dict:
                               orient_sigma=(10 * DEG, 10 * DEG, 10 * DEG), nx=256, ny=256))
 
 
+def lamellar_caille() -> dict:
+    """Multilamellar phase: head-tail bilayers (tails 14 A, SLD -0.4e-6;
+    heads 8 A, 3e-6; solvent 6.3e-6) stacked 30 at a time with repeat
+    distance 70 A and Caille parameter 0.1, volume fraction 0.1, 256x256,
+    1e9 neutrons."""
+    return dict(name="lamellar_caille", n=10**9, seed=27, exp_id=0,
+                params=params(kind="lamellar_hg_stack_caille", size=(14.0, 8.0, 70.0), sld=(-0.4e-6, 3e-6, 6.3e-6),
+                              extra=(30.0, 0.1, 0.0, 0.0), phi=0.1, nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -356,6 +368,7 @@ WORKLOADS = {
     "sticky_coreshell": sticky_coreshell,
     "mass_surface_fractal": mass_surface_fractal,
     "oriented_superball": oriented_superball,
+    "lamellar_caille": lamellar_caille,
 }
 
 

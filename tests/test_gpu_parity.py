@@ -308,6 +308,16 @@ PER_NEUTRON = {
                                       orient_mean=(0.4, 0.9, 0.3)), 10011),
     "superball_cubic_small_q": (W.params(kind="superball", size=(8.0, 0, 0), extra=(40.0, 0, 0, 0), quad_n=7,
                                          orient_kind="uniform_angles"), 10011),
+    # lamellae
+    "lamellar_caille": (W.workload("lamellar_caille")["params"], 50021),
+    "lamellar_hg": (W.params(kind="lamellar_hg", size=(12.0, 9.0, 0), sld=(-0.3e-6, 2.5e-6, 6.3e-6), phi=0.05),
+                    30011),
+    "lamellar_stack_caille": (W.params(kind="lamellar_stack_caille", size=(35.0, 90.0, 0), sld=(1e-6, 0, 6.3e-6),
+                                       extra=(12.0, 0.3, 0, 0), phi=0.2), 30011),
+    "lamellar_stack_paracrystal": (W.params(kind="lamellar_stack_paracrystal", size=(30.0, 75.0, 0),
+                                            sld=(1e-6, 0, 6.3e-6), extra=(20.0, 6.0, 0, 0), phi=0.2), 30011),
+    "quad_lamellar_paracrystal": (W.params(kind="lamellar_stack_paracrystal", mode="quad", size=(30.0, 75.0, 0),
+                                           sld=(1e-6, 0, 6.3e-6), extra=(5.0, 3.0, 0, 0), phi=0.2), 3011),
 }
 
 
@@ -338,7 +348,7 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "fractal_poly", "polymer_excl_volume", "broad_peak", "oriented_elliptical_cylinder",
              "bicelle_poly_iso", "cs_parallelepiped_gauss", "stacked_disks_gauss", "oriented_fcc_paracrystal",
              "mass_surface_fractal", "gel_fit", "sticky_coreshell", "square_well_poly_sphere",
-             "oriented_superball"]
+             "oriented_superball", "lamellar_caille", "lamellar_hg", "lamellar_stack_paracrystal"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -473,7 +483,7 @@ def test_full_size_coreshell(S):
 
 @pytest.mark.parametrize("name", ["oriented_cylinder", "oriented_ellipsoid", "oriented_barbell",
                                   "oriented_hollow_prism", "micelle_py", "oriented_core_shell_cylinder",
-                                  "teubner_strey", "sticky_coreshell", "mass_surface_fractal"])
+                                  "teubner_strey", "sticky_coreshell", "mass_surface_fractal", "lamellar_caille"])
 def test_full_size_sampled(S, name):
     """1e9- and 1e8-neutron workloads: the full run equals the sum of its chunks, and
     windows spread over the whole index range match the oracle neutron by
