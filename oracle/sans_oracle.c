@@ -75,7 +75,9 @@ typedef struct {
                               lamellae: 52 bilayers with head and tail
                               groups, 53 stacks with Caille fluctuations,
                               54 head-tail bilayers in Caille stacks, 55
-                              paracrystalline stacks                         */
+                              paracrystalline stacks; oriented: 56
+                              elliptical bicelle with a belt and rough
+                              interfaces                                    */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -702,6 +704,22 @@ static double amplitude(int kind, const double s[3], double shell, const double 
         double outer = ORC_PI * rr * (xr * s[0] + shell) * lf * orc_sinc(0.5 * qc * lf) * orc_lambda1(a2);
         return (sld[0] - rf) * core + (rf - sld[1]) * faces + (sld[1] - sld[2]) * outer;
     }
+    case 56: { /* elliptical bicelle with a belt: an elliptic core (semi-axes R,
+                  x R; length L), face layers of thickness t_f = extra[0] (SLD
+                  extra[1]) over the core's cross-section at both ends, a belt
+                  of thickness shell (SLD sld[1]) around the core only (length
+                  L); rough interfaces damp the amplitude by exp(-(q sigma)^2/2),
+                  sigma = extra[3] */
+        double xr = extra[2], tf = extra[0], rf = extra[1], t = shell;
+        double ra = s[0], rb = xr * s[0], len = s[1], lf = len + 2.0 * tf;
+        double a1 = sqrt((ra * qa) * (ra * qa) + (rb * qb) * (rb * qb));
+        double a2 = sqrt(((ra + t) * qa) * ((ra + t) * qa) + ((rb + t) * qb) * ((rb + t) * qb));
+        double core = ORC_PI * ra * rb * len * orc_sinc(0.5 * qc * len) * orc_lambda1(a1);
+        double faces = ORC_PI * ra * rb * lf * orc_sinc(0.5 * qc * lf) * orc_lambda1(a1);
+        double belt = ORC_PI * (ra + t) * (rb + t) * len * orc_sinc(0.5 * qc * len) * orc_lambda1(a2);
+        double amp = (sld[0] - rf - sld[1] + sld[2]) * core + (rf - sld[2]) * faces + (sld[1] - sld[2]) * belt;
+        return amp * exp(-0.5 * q * q * extra[3] * extra[3]);
+    }
     case 45: { /* one disk of the stack: a core of radius R, thickness s1, with
                   layers of thickness shell on both faces */
         double qab2 = q * q - qc * qc;
@@ -1082,7 +1100,7 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
 }
 
 /* Orientation matters (the particles from 2 to 12 but the micelle). */
-static int anisotropic(int kind) { return (kind >= 2 && kind != 8 && kind <= 12) || (kind >= 41 && kind <= 48) || kind == 51; }
+static int anisotropic(int kind) { return (kind >= 2 && kind != 8 && kind <= 12) || (kind >= 41 && kind <= 48) || kind == 51 || kind == 56; }
 
 /* Sizes scaled by the relative size draw y according to the mask. */
 static void scaled_sizes(const orc_params* p, double y, double s[3])
@@ -1222,6 +1240,14 @@ double orc_mean_volume(const orc_params* p)
         double al[3] = {s[0], xr * s[0], s[1]}, be[3] = {p->shell, p->shell, 2.0 * p->extra[0]};
         int bb[3] = {b0, b0, b1};
         return ORC_PI * prod_moment(p, al, be, bb, 3);
+    }
+    case 56: { /* core and belt pi (R + t)(x R + t) L plus the two faces 2 pi x R^2 t_f */
+        double xr = p->extra[2];
+        double al[3] = {s[0], xr * s[0], s[1]}, be[3] = {p->shell, p->shell, 0.0};
+        int bb[3] = {b0, b0, b1};
+        double af[2] = {s[0], xr * s[0]}, bf[2] = {0.0, 0.0};
+        int cf[2] = {b0, b0};
+        return ORC_PI * prod_moment(p, al, be, bb, 3) + 2.0 * ORC_PI * p->extra[0] * prod_moment(p, af, bf, cf, 2);
     }
     case 45: { /* one disk: pi R^2 (core + two layers) */
         double al[3] = {s[0], s[0], s[1]}, be[3] = {0.0, 0.0, 2.0 * p->shell};

@@ -1663,3 +1663,50 @@ def test_caille_damps_the_higher_orders_more(orc):
     g = 0.57721566490153286061
     want = (1 + 2 * sum((1 - k / n) * (math.pi * k) ** (-0.1) * math.exp(-0.1 * g) for k in range(1, n))) / n
     assert ratios[0] == pytest.approx(want, rel=1e-10)
+
+
+# ---------------------------------------------------------------- belt-rough elliptical bicelle
+
+def _amp(orc, p, qv):
+    return orc.amplitude(p, math.sqrt(sum(c * c for c in qv)), qv)
+
+
+@pytest.mark.parametrize("qv", [(0.0, 0.0, 0.0), (0.02, 0.01, 0.03), (0.05, -0.03, 0.01), (0.0, 0.07, 0.09)])
+def test_belt_bicelle_reductions_and_roughness(orc, qv):
+    """Without face layers the belt is the elliptical bicelle's rim (which
+    then covers only the core); without a belt it is the elliptical bicelle
+    with faces only; roughness multiplies the amplitude by exp(-(q sigma)^2/2)."""
+    sld = (1e-6, 4e-6, 6.3e-6)
+    base = dict(size=(25.0, 40.0, 0.0), sld=sld, orient_mean=(0.0, 0.0, 0.0))
+    belt = W.params(kind="core_shell_bicelle_elliptical_belt_rough", shell=6.0, extra=(0.0, 2.5e-6, 1.7, 0.0), **base)
+    ell = W.params(kind="core_shell_bicelle_elliptical", shell=6.0, extra=(0.0, 2.5e-6, 1.7, 0.0), **base)
+    assert _amp(orc, belt, qv) == pytest.approx(_amp(orc, ell, qv), rel=1e-12, abs=1e-30)
+    belt0 = W.params(kind="core_shell_bicelle_elliptical_belt_rough", shell=0.0, extra=(5.0, 2.5e-6, 1.7, 0.0), **base)
+    ell0 = W.params(kind="core_shell_bicelle_elliptical", shell=0.0, extra=(5.0, 2.5e-6, 1.7, 0.0), **base)
+    assert _amp(orc, belt0, qv) == pytest.approx(_amp(orc, ell0, qv), rel=1e-12, abs=1e-30)
+    rough = W.params(kind="core_shell_bicelle_elliptical_belt_rough", shell=6.0, extra=(5.0, 2.5e-6, 1.7, 3.0), **base)
+    smooth = W.params(kind="core_shell_bicelle_elliptical_belt_rough", shell=6.0, extra=(5.0, 2.5e-6, 1.7, 0.0), **base)
+    q2 = sum(c * c for c in qv)
+    assert _amp(orc, rough, qv) == pytest.approx(_amp(orc, smooth, qv) * math.exp(-0.5 * q2 * 9.0), rel=1e-13, abs=1e-30)
+
+
+def test_belt_bicelle_forward_amplitude_and_volume(orc):
+    """F(0) is the sum of contrast times volume over the three regions (core,
+    the two faces, the belt), and the mean volume is theirs over the Schulz
+    sizes (quadrature)."""
+    from scipy import integrate, stats
+    R, L, t, tf, x = 25.0, 40.0, 6.0, 5.0, 1.7
+    rc, rb, rf, rs = 1e-6, 4e-6, 2.5e-6, 6.3e-6
+    p = W.params(kind="core_shell_bicelle_elliptical_belt_rough", size=(R, L, 0.0), shell=t, sld=(rc, rb, rs),
+                 extra=(tf, rf, x, 2.0))
+    vcore = math.pi * R * x * R * L
+    vfaces = 2 * math.pi * R * x * R * tf
+    vbelt = math.pi * (R + t) * (x * R + t) * L - vcore
+    assert _amp(orc, p, (0.0, 0.0, 0.0)) == pytest.approx((rc - rs) * vcore + (rf - rs) * vfaces + (rb - rs) * vbelt,
+                                                          rel=1e-13)
+    pp = dict(p, poly=0.2, poly_mask=3)
+    z = 1 / 0.04
+    g = stats.gamma(a=z, scale=1 / z)
+    vol = lambda y: math.pi * (R * y + t) * (x * R * y + t) * L * y + 2 * math.pi * x * (R * y) ** 2 * tf
+    want, _ = integrate.quad(lambda y: vol(y) * g.pdf(y), 0, 5, epsabs=0, epsrel=1e-12, limit=200)
+    assert orc.mean_volume(pp) == pytest.approx(want, rel=1e-9)
