@@ -207,9 +207,18 @@ typedef enum {
     SANS_LAMELLAR_HG_STACK_CAILLE = 54, /* head-tail bilayers (size[0],
                                     size[1], as SANS_LAMELLAR_HG) in a Caille
                                     stack of repeat distance size[2]          */
-    SANS_LAMELLAR_STACK_PARACRYSTAL = 55 /* slabs of thickness size[0], spacings
+    SANS_LAMELLAR_STACK_PARACRYSTAL = 55, /* slabs of thickness size[0], spacings
                                     Gaussian of mean size[1] and width
                                     extra[1] >= 0 (A)                         */
+    SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH = 56 /* oriented: elliptic
+                                    core (semi-axes size[0] along A,
+                                    extra[2] size[0] along B; length size[1]
+                                    along C); face layers extra[0] thick (SLD
+                                    extra[1]) over the core's cross-section; a
+                                    belt of thickness shell (SLD sld[1])
+                                    around the core's length only; interface
+                                    roughness extra[3] >= 0 (A) damps F by
+                                    exp(-(q extra[3])^2 / 2)                  */
 } sans_kind;
 
 /* Structure factor S(q) of the particles (when sq_phi > 0): volume fraction

@@ -77,7 +77,7 @@ typedef struct {
                               54 head-tail bilayers in Caille stacks, 55
                               paracrystalline stacks; oriented: 56
                               elliptical bicelle with a belt and rough
-                              interfaces                                    */
+                              interfaces; 57 raspberry (isotropic)          */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -982,6 +982,22 @@ static double sphere_family_f2(const orc_params* p, const double s[3], double q)
         for (int k = 1; k < n; ++k) pairs += 2.0 * (n - k) * orc_sinc(q * k * d);
         return f * f * pairs;
     }
+    case 57: {
+        /* raspberry: a large sphere (radius s0, sld[0]) carrying N = extra[0]
+           small spheres (radius s1, sld[1]) whose centres sit at D = s0 + s1
+           (1 - 2 delta) from its centre (delta = extra[1] in [0, 1], the depth
+           of penetration in small-sphere diameters), at independent uniform
+           positions on that sphere.  Averaged over orientations and positions
+           (Debye's pair sum): F_L^2 + N F_S^2 + 2 N F_L F_S <sinc> + N (N - 1)
+           F_S^2 <sinc>^2 with <sinc> = sin(qD)/(qD), the average of exp(i Q.r)
+           over a sphere of radius D */
+        double n = p->extra[0];
+        double fl = drho * vol_sphere(s[0]) * orc_sph(q * s[0]);
+        double fs = sh * vol_sphere(s[1]) * orc_sph(q * s[1]);
+        double dd = s[0] + s[1] * (1.0 - 2.0 * p->extra[1]);
+        double c = orc_sinc(q * dd);
+        return fl * fl + n * fs * fs + 2.0 * n * fl * fs * c + n * (n - 1.0) * fs * fs * c * c;
+    }
     }
     return 0.0;
 }
@@ -1046,7 +1062,7 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
     if (shape_independent(p->kind)) return shape_independent_iq(p, s, q);
     if (lamellar(p->kind)) return lamellar_iq(p, s, q);
     if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
-    if (p->kind >= 25 && p->kind <= 28) return sphere_family_f2(p, s, q);
+    if ((p->kind >= 25 && p->kind <= 28) || p->kind == 57) return sphere_family_f2(p, s, q);
     if (p->kind == 45) {
         /* stacked disks: N = extra[0] disks, spacing d = s1 + 2 shell along C with
            Gaussian spread extra[1]: F^2 times 1 + (2/N) sum_k (N - k) cos(k d Q_C)
@@ -1216,6 +1232,8 @@ double orc_mean_volume(const orc_params* p)
         return 4.0 / 3.0 * ORC_PI * (r * r * r * size_moment(p, 3) + 3.0 * r * r * t * size_moment(p, 2)
                                       + 3.0 * r * t * t * size_moment(p, 1) + t * t * t);
     }
+    case 57: /* raspberry: the large sphere and its N small ones */
+        return vol_sphere(s[0]) * size_moment(p, (p->poly_mask & 1) ? 3 : 0) + p->extra[0] * vol_sphere(s[1]);
     case 28: /* linear pearls: n spheres */
         return p->extra[0] * vol_sphere(s[0]) * size_moment(p, b0 ? 3 : 0);
     case 8: /* N chains, each a core block and a corona chain */

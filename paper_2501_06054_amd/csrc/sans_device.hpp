@@ -140,6 +140,8 @@ struct TraceArgs {
     // elliptical bicelle: cross-section ratio; stacked disks: spacing d, spread
     // sigma, count (sf_n); paracrystals: primitive vectors (A), (g D)^2 / 2
     double bi_x, sd_d, sd_sig, pc_v[3][3], pc_b;
+    // belt bicelle: -sigma^2 / 2 of the interface roughness
+    double bi_rough;
     // lamellae: 2 pi / delta and the Caille parameter (the repeat distance,
     // spacing spread and count in sd_d, sd_sig, sf_n; the Caille exponents'
     // gamma + ln(pi n) in cap_nodes)
@@ -564,7 +566,8 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kCoreShellBicelle = 42, kCoreShellParallelepiped = 43, kCoreShellBicelleElliptical = 44,
               kStackedDisks = 45, kScParacrystal = 46, kBccParacrystal = 47, kFccParacrystal = 48,
               kMassSurfaceFractal = 49, kGelFit = 50, kSuperball = 51, kLamellarHg = 52,
-              kLamellarStackCaille = 53, kLamellarHgStackCaille = 54, kLamellarStackParacrystal = 55 };
+              kLamellarStackCaille = 53, kLamellarHgStackCaille = 54, kLamellarStackParacrystal = 55,
+              kBicelleBeltRough = 56 };
 
 // Randomly oriented lamellae: the weight per unit volume fraction.
 template <int KIND>
@@ -592,7 +595,8 @@ constexpr bool kSphereFamily = (KIND >= kFuzzySphere && KIND <= kLinearPearls) |
 // thick hollow prism, but the micelle).
 template <int KIND>
 constexpr bool kAniso = (KIND >= kCylinder && KIND <= kHollowPrismThick && KIND != kMicelle)
-                        || (KIND >= kEllipticalCylinder && KIND <= kFccParacrystal) || KIND == kSuperball;
+                        || (KIND >= kEllipticalCylinder && KIND <= kFccParacrystal) || KIND == kSuperball
+                        || KIND == kBicelleBeltRough;
 
 // Bodies of revolution about C: cylinders (plain, hollow, core-shell),
 // barbell, capped cylinder (only the axis projection Q.C and Q_AB enter, the
@@ -1151,6 +1155,19 @@ __device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, doub
         const float faces = (float)ra * (float)rb * (float)lf * ends * d1;
         const float outer = (float)oa * (float)ob * (float)lf * ends * d2;
         return (float)kPi * (a.bi_c[0] * core + a.bi_c[1] * faces + a.bi_c[2] * outer);
+    } else if constexpr (KIND == kBicelleBeltRough) {
+        // core R x xR x L, faces over the core's cross-section (L + 2 t_f), the
+        // belt (R + t) x (xR + t) x L; roughness exp(-(q sigma)^2 / 2)
+        const double ra = s[0], rb = a.bi_x * s[0], oa = ra + a.shell, ob = rb + a.shell;
+        const double lf = __builtin_fma(2.0, a.cs_face, s[1]);
+        const float d1 = lambda1_f((float)sqrt((ra * qa) * (ra * qa) + (rb * qb) * (rb * qb)));
+        const float d2 = lambda1_f((float)sqrt((oa * qa) * (oa * qa) + (ob * qb) * (ob * qb)));
+        const float mid = sinc_d(0.5 * qc * s[1]);
+        const float core = (float)ra * (float)rb * (float)s[1] * mid * d1;
+        const float faces = (float)ra * (float)rb * (float)lf * sinc_d(0.5 * qc * lf) * d1;
+        const float belt = (float)oa * (float)ob * (float)s[1] * mid * d2;
+        const float rough = __expf((float)(q * q * a.bi_rough));
+        return (float)kPi * rough * (a.bi_c[0] * core + a.bi_c[1] * faces + a.bi_c[2] * belt);
     } else if constexpr (KIND == kStackedDisks) {
         // one disk: core (R, s1) and core + face layers (R, s1 + 2 shell)
         const double qab = sqrt(fmax(__builtin_fma(q, q, -qc * qc), 0.0));
@@ -1268,6 +1285,18 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
         const float faces = ra * rb * lf * ends * d1;
         const float outer = oa * ob * lf * ends * d2;
         return (float)kPi * (a.bi_c[0] * core + a.bi_c[1] * faces + a.bi_c[2] * outer);
+    } else if constexpr (KIND == kBicelleBeltRough) {
+        const float ra = s[0], rb = (float)a.bi_x * s[0], oa = ra + a.fshell, ob = rb + a.fshell;
+        const float lf = __builtin_fmaf(2.0f, a.fcs_face, s[1]);
+        const float xa1 = ra * qa, xb1 = rb * qb, xa2 = oa * qa, xb2 = ob * qb;
+        const float d1 = lambda1_f(sqrtf(__builtin_fmaf(xa1, xa1, xb1 * xb1)));
+        const float d2 = lambda1_f(sqrtf(__builtin_fmaf(xa2, xa2, xb2 * xb2)));
+        const float mid = sinc_f(0.5f * qc * s[1]);
+        const float core = ra * rb * s[1] * mid * d1;
+        const float faces = ra * rb * lf * sinc_f(0.5f * qc * lf) * d1;
+        const float belt = oa * ob * s[1] * mid * d2;
+        const float rough = __expf(q * q * (float)a.bi_rough);
+        return (float)kPi * rough * (a.bi_c[0] * core + a.bi_c[1] * faces + a.bi_c[2] * belt);
     } else if constexpr (KIND == kStackedDisks) {
         const float qab = sqrtf(fmaxf(__builtin_fmaf(q, q, -qc * qc), 0.0f));
         const float r = s[0], lo = __builtin_fmaf(2.0f, a.fshell, s[1]), disc = lambda1_f(qab * r);

@@ -549,7 +549,8 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 52: batch_tile<52>(a, tl.first, tl.count, hist, tab); break;
         case 53: batch_tile<53>(a, tl.first, tl.count, hist, tab); break;
         case 54: batch_tile<54>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<55>(a, tl.first, tl.count, hist, tab); break;
+        case 55: batch_tile<55>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<56>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -838,6 +839,7 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(53)
         SANS_CASE(54)
         SANS_CASE(55)
+        SANS_CASE(56)
     }
 #undef SANS_CASE
     return nullptr;
@@ -908,6 +910,7 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(53)
         SANS_CASE(54)
         SANS_CASE(55)
+        SANS_CASE(56)
     }
 #undef SANS_CASE
     return nullptr;
@@ -975,6 +978,7 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(53)
         SANS_CASE(54)
         SANS_CASE(55)
+        SANS_CASE(56)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1042,6 +1046,7 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(53)
         SANS_CASE(54)
         SANS_CASE(55)
+        SANS_CASE(56)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1106,6 +1111,7 @@ PqFn pick_pq(int kind)
     case 53: return k_pq_avg<53>;
     case 54: return k_pq_avg<54>;
     case 55: return k_pq_avg<55>;
+    case 56: return k_pq_avg<56>;
     }
     return nullptr;
 }
@@ -1169,7 +1175,8 @@ bool is_sphere_family(int kind)
 bool is_aniso(int kind)
 {
     return (kind >= SANS_CYLINDER && kind <= SANS_HOLLOW_PRISM_THICK && kind != SANS_POLYMER_MICELLE)
-           || (kind >= SANS_ELLIPTICAL_CYLINDER && kind <= SANS_FCC_PARACRYSTAL) || kind == SANS_SUPERBALL;
+           || (kind >= SANS_ELLIPTICAL_CYLINDER && kind <= SANS_FCC_PARACRYSTAL) || kind == SANS_SUPERBALL
+           || kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH;
 }
 
 // Floats of the per-model node rule in device memory: the end caps' rule
@@ -1229,7 +1236,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 55) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 56) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -1248,7 +1255,8 @@ int validate(const sans_params* p)
                            || p->kind == SANS_STACKED_DISKS || p->kind == SANS_SC_PARACRYSTAL
                            || p->kind == SANS_BCC_PARACRYSTAL || p->kind == SANS_FCC_PARACRYSTAL
                            || p->kind == SANS_LAMELLAR_HG || p->kind == SANS_LAMELLAR_STACK_CAILLE
-                           || p->kind == SANS_LAMELLAR_STACK_PARACRYSTAL;
+                           || p->kind == SANS_LAMELLAR_STACK_PARACRYSTAL
+                           || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH;
     int nsize = (p->kind <= 1 || p->kind == SANS_SUPERBALL) ? 1 : (two_sizes ? 2 : 3);
     if (is_shape_independent(p->kind))
         nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK
@@ -1270,6 +1278,11 @@ int validate(const sans_params* p)
             return fail(SANS_E_UNSUPPORTED, "barbell / capped cylinder: poly_mask must be 7 (all sizes)");
         if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
     }
+    if (p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH
+        && !(p->shell >= 0.0 && finite(p->shell) && p->extra[0] >= 0.0 && finite(p->extra[0]) && finite(p->extra[1])
+             && p->extra[2] > 0.0 && finite(p->extra[2]) && p->extra[3] >= 0.0 && finite(p->extra[3])))
+        return fail(SANS_E_INVALID_ARG, "belt bicelle: need belt shell >= 0, face thickness extra[0] >= 0, a finite "
+                                        "face SLD extra[1], ratio extra[2] > 0 and roughness extra[3] >= 0");
     if (p->kind >= SANS_LAMELLAR_HG && p->kind <= SANS_LAMELLAR_STACK_PARACRYSTAL) {
         if (p->kind != SANS_LAMELLAR_HG
             && !(p->extra[0] >= 1.0 && p->extra[0] <= 1000.0 && p->extra[0] == std::floor(p->extra[0])))
@@ -1579,11 +1592,20 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
         }
     }
     if (p->kind == SANS_CORE_SHELL_CYLINDER || p->kind == SANS_CORE_SHELL_BICELLE
-        || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL) {
+        || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH) {
         a.cs_face = p->extra[0];
         a.fcs_face = (float)p->extra[0];
     }
-    if (p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL) a.bi_x = p->extra[2];
+    if (p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH)
+        a.bi_x = p->extra[2];
+    if (p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH) {
+        // contrasts of the core, face and belt regions (core - face - belt +
+        // solvent, face - solvent, belt - solvent) and -sigma^2 / 2
+        a.bi_c[0] = (float)(p->sld[0] - p->extra[1] - p->sld[1] + p->sld[2]);
+        a.bi_c[1] = (float)(p->extra[1] - p->sld[2]);
+        a.bi_c[2] = (float)(p->sld[1] - p->sld[2]);
+        a.bi_rough = -0.5 * p->extra[3] * p->extra[3];
+    }
     if (p->kind == SANS_STACKED_DISKS) {
         a.sf_n = (int32_t)p->extra[0];
         a.sd_d = p->size[1] + 2.0 * p->shell;

@@ -318,6 +318,14 @@ PER_NEUTRON = {
                                             sld=(1e-6, 0, 6.3e-6), extra=(20.0, 6.0, 0, 0), phi=0.2), 30011),
     "quad_lamellar_paracrystal": (W.params(kind="lamellar_stack_paracrystal", mode="quad", size=(30.0, 75.0, 0),
                                            sld=(1e-6, 0, 6.3e-6), extra=(5.0, 3.0, 0, 0), phi=0.2), 3011),
+    # elliptical bicelle with a belt and rough interfaces
+    "belt_bicelle_gauss": (W.params(kind="core_shell_bicelle_elliptical_belt_rough", size=(25, 40, 0), shell=6.0,
+                                    sld=(1e-6, 4e-6, 6.3e-6), extra=(5.0, 2.5e-6, 1.7, 3.0), orient_kind="gaussian",
+                                    orient_mean=(1.1, 0.4, 0.6), orient_sigma=(0.15, 0.15, 0.3), poly=0.1,
+                                    poly_mask=3), 30011),
+    "quad_belt_bicelle": (W.params(kind="core_shell_bicelle_elliptical_belt_rough", mode="quad", size=(25, 40, 0),
+                                   shell=6.0, sld=(1e-6, 4e-6, 6.3e-6), extra=(5.0, 2.5e-6, 1.7, 3.0),
+                                   orient_kind="isotropic", quad_n=40), 301),
 }
 
 
@@ -348,7 +356,8 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "fractal_poly", "polymer_excl_volume", "broad_peak", "oriented_elliptical_cylinder",
              "bicelle_poly_iso", "cs_parallelepiped_gauss", "stacked_disks_gauss", "oriented_fcc_paracrystal",
              "mass_surface_fractal", "gel_fit", "sticky_coreshell", "square_well_poly_sphere",
-             "oriented_superball", "lamellar_caille", "lamellar_hg", "lamellar_stack_paracrystal"]
+             "oriented_superball", "lamellar_caille", "lamellar_hg", "lamellar_stack_paracrystal",
+             "belt_bicelle_gauss"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)

@@ -1710,3 +1710,35 @@ def test_belt_bicelle_forward_amplitude_and_volume(orc):
     vol = lambda y: math.pi * (R * y + t) * (x * R * y + t) * L * y + 2 * math.pi * x * (R * y) ** 2 * tf
     want, _ = integrate.quad(lambda y: vol(y) * g.pdf(y), 0, 5, epsabs=0, epsrel=1e-12, limit=200)
     assert orc.mean_volume(pp) == pytest.approx(want, rel=1e-9)
+
+
+# ---------------------------------------------------------------- raspberry
+
+def _sph_amp(drho, r, q):
+    x = q * r
+    return drho * 4 / 3 * math.pi * r ** 3 * (3 * (math.sin(x) - x * math.cos(x)) / x ** 3 if x > 0 else 1.0)
+
+
+@pytest.mark.parametrize("q", [0.0, 0.004, 0.03, 0.08])
+def test_raspberry_pair_sum(orc, q):
+    """Debye's pair sum over the large sphere and two small ones at
+    independent uniform positions on the sphere of radius D: the small-small
+    term is the average of sinc(q |r1 - r2|) over the angle between them (by
+    quadrature), the large-small one sinc(q D); no small spheres is the
+    sphere; at q = 0 everything adds coherently."""
+    from scipy import integrate
+    rl, rs, delta = 60.0, 12.0, 0.3
+    sl, ss, sv = 1e-6, 4e-6, 6.3e-6
+    d = rl + rs * (1 - 2 * delta)
+    fl, fs = _sph_amp(sl - sv, rl, q), _sph_amp(ss - sv, rs, q)
+    sinc = lambda x: math.sin(x) / x if x > 0 else 1.0
+    pair, _ = integrate.quad(lambda t: sinc(q * 2 * d * math.sin(t / 2)) * math.sin(t) / 2, 0, math.pi,
+                             epsabs=0, epsrel=1e-13, limit=200)
+    want2 = fl * fl + 2 * fs * fs + 4 * fl * fs * sinc(q * d) + 2 * fs * fs * pair
+    p2 = W.params(kind="raspberry", size=(rl, rs, 0.0), sld=(sl, ss, sv), extra=(2.0, delta, 0, 0))
+    assert orc.form_f2(p2, q, (0.0, 0.0, q)) == pytest.approx(want2, rel=1e-11)
+    p0 = W.params(kind="raspberry", size=(rl, rs, 0.0), sld=(sl, ss, sv), extra=(0.0, delta, 0, 0))
+    assert orc.form_f2(p0, q, (0.0, 0.0, q)) == pytest.approx(fl * fl, rel=1e-14)
+    if q == 0.0:
+        p9 = W.params(kind="raspberry", size=(rl, rs, 0.0), sld=(sl, ss, sv), extra=(9.0, delta, 0, 0))
+        assert orc.form_f2(p9, 0.0, (0.0, 0.0, 0.0)) == pytest.approx((fl + 9 * fs) ** 2, rel=1e-13)
