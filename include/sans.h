@@ -210,7 +210,7 @@ typedef enum {
     SANS_LAMELLAR_STACK_PARACRYSTAL = 55, /* slabs of thickness size[0], spacings
                                     Gaussian of mean size[1] and width
                                     extra[1] >= 0 (A)                         */
-    SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH = 56 /* oriented: elliptic
+    SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH = 56, /* oriented: elliptic
                                     core (semi-axes size[0] along A,
                                     extra[2] size[0] along B; length size[1]
                                     along C); face layers extra[0] thick (SLD
@@ -219,6 +219,14 @@ typedef enum {
                                     around the core's length only; interface
                                     roughness extra[3] >= 0 (A) damps F by
                                     exp(-(q extra[3])^2 / 2)                  */
+    SANS_RASPBERRY = 57          /* isotropic: a large sphere (radius size[0],
+                                    sld[0]) carrying extra[0] >= 0 small
+                                    spheres (radius size[1], sld[1]) centred
+                                    size[0] + size[1] (1 - 2 extra[1]) from
+                                    its centre (extra[1] in [0, 1]: the depth
+                                    of penetration in small-sphere diameters),
+                                    at independent uniform positions;
+                                    polydispersity scales size[0] only       */
 } sans_kind;
 
 /* Structure factor S(q) of the particles (when sq_phi > 0): volume fraction

@@ -140,8 +140,10 @@ struct TraceArgs {
     // elliptical bicelle: cross-section ratio; stacked disks: spacing d, spread
     // sigma, count (sf_n); paracrystals: primitive vectors (A), (g D)^2 / 2
     double bi_x, sd_d, sd_sig, pc_v[3][3], pc_b;
-    // belt bicelle: -sigma^2 / 2 of the interface roughness
+    // belt bicelle: -sigma^2 / 2 of the interface roughness; raspberry: the
+    // number of small spheres (their centres' offset beyond R in sf_gap)
     double bi_rough;
+    float rb_n;
     // lamellae: 2 pi / delta and the Caille parameter (the repeat distance,
     // spacing spread and count in sd_d, sd_sig, sf_n; the Caille exponents'
     // gamma + ln(pi n) in cap_nodes)
@@ -567,7 +569,7 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kStackedDisks = 45, kScParacrystal = 46, kBccParacrystal = 47, kFccParacrystal = 48,
               kMassSurfaceFractal = 49, kGelFit = 50, kSuperball = 51, kLamellarHg = 52,
               kLamellarStackCaille = 53, kLamellarHgStackCaille = 54, kLamellarStackParacrystal = 55,
-              kBicelleBeltRough = 56 };
+              kBicelleBeltRough = 56, kRaspberry = 57 };
 
 // Randomly oriented lamellae: the weight per unit volume fraction.
 template <int KIND>
@@ -589,7 +591,7 @@ constexpr bool kShapeIndependent = (KIND >= kGuinier && KIND <= kGaussLorentzGel
 // fractal aggregates of spheres).
 template <int KIND>
 constexpr bool kSphereFamily = (KIND >= kFuzzySphere && KIND <= kLinearPearls) || KIND == kFractal
-                               || KIND == kFractalCoreShell;
+                               || KIND == kFractalCoreShell || KIND == kRaspberry;
 
 // Orientation enters the weight (the particles from the cylinder to the
 // thick hollow prism, but the micelle).
@@ -1006,6 +1008,15 @@ __device__ __forceinline__ float sphere_family_f2(const TraceArgs& a, double R, 
             sq = 1.0 + num * exp(-d * log(q * r0) - 0.5 * (d - 1.0) * log1p(1.0 / (qx * qx)));
         }
         return f * f * (float)sq;
+    } else if constexpr (KIND == kRaspberry) {
+        // (F_L + N F_S c)^2 + N F_S^2 (1 - c^2), c = sinc(q D), D = R + offset:
+        // the pair sum averaged over independent positions on the sphere of radius D
+        const float r = (float)R, rs = (float)a.size[1], n = a.rb_n;
+        const float fl = a.contrast * k43pi * r * r * r * sph3j_d(q * R);
+        const float fs = a.cs_shell * k43pi * rs * rs * rs * sph3j_d(q * a.size[1]);
+        const float c = sinc_d(q * (R + a.sf_gap));
+        const float t = __builtin_fmaf(n * fs, c, fl);
+        return __builtin_fmaf(t, t, n * fs * fs * __builtin_fmaf(-c, c, 1.0f));
     } else {
         const float r = (float)R;
         const float fs = a.contrast * k43pi * r * r * r * sph3j_d(q * R);

@@ -550,7 +550,8 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 53: batch_tile<53>(a, tl.first, tl.count, hist, tab); break;
         case 54: batch_tile<54>(a, tl.first, tl.count, hist, tab); break;
         case 55: batch_tile<55>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<56>(a, tl.first, tl.count, hist, tab); break;
+        case 56: batch_tile<56>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<57>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -840,6 +841,7 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(54)
         SANS_CASE(55)
         SANS_CASE(56)
+        SANS_CASE(57)
     }
 #undef SANS_CASE
     return nullptr;
@@ -911,6 +913,7 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(54)
         SANS_CASE(55)
         SANS_CASE(56)
+        SANS_CASE(57)
     }
 #undef SANS_CASE
     return nullptr;
@@ -979,6 +982,7 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(54)
         SANS_CASE(55)
         SANS_CASE(56)
+        SANS_CASE(57)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1047,6 +1051,7 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(54)
         SANS_CASE(55)
         SANS_CASE(56)
+        SANS_CASE(57)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1112,6 +1117,7 @@ PqFn pick_pq(int kind)
     case 54: return k_pq_avg<54>;
     case 55: return k_pq_avg<55>;
     case 56: return k_pq_avg<56>;
+    case 57: return k_pq_avg<57>;
     }
     return nullptr;
 }
@@ -1167,7 +1173,7 @@ bool is_shape_independent(int kind)
 bool is_sphere_family(int kind)
 {
     return (kind >= SANS_FUZZY_SPHERE && kind <= SANS_LINEAR_PEARLS) || kind == SANS_FRACTAL
-           || kind == SANS_FRACTAL_CORE_SHELL;
+           || kind == SANS_FRACTAL_CORE_SHELL || kind == SANS_RASPBERRY;
 }
 
 // Orientation enters the weight (the particles from the cylinder to the thick
@@ -1236,7 +1242,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 56) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 57) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -1268,7 +1274,7 @@ int validate(const sans_params* p)
                     ? 2
                     : 1;
     if (is_sphere_family(p->kind))
-        nsize = (p->kind == SANS_FRACTAL || p->kind == SANS_FRACTAL_CORE_SHELL) ? 2 : 1;
+        nsize = (p->kind == SANS_FRACTAL || p->kind == SANS_FRACTAL_CORE_SHELL || p->kind == SANS_RASPBERRY) ? 2 : 1;
     for (int k = 0; k < nsize; ++k)
         if (!(p->size[k] > 0.0) || !finite(p->size[k])) return fail(SANS_E_INVALID_ARG, "size must be > 0");
     if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
@@ -1404,6 +1410,13 @@ int validate(const sans_params* p)
             return fail(SANS_E_INVALID_ARG, "need a gap size[1] >= 0 and an integer count extra[0] in 1..1000");
         if (p->kind == SANS_MULTILAYER_VESICLE && p->poly > 0.0 && p->poly_mask != 0)
             return fail(SANS_E_UNSUPPORTED, "multilayer vesicle: monodisperse only");
+        if (p->kind == SANS_RASPBERRY) {
+            if (!(p->extra[0] >= 0.0 && p->extra[0] <= 1e4 && p->extra[1] >= 0.0 && p->extra[1] <= 1.0))
+                return fail(SANS_E_INVALID_ARG, "raspberry: need a count extra[0] in [0, 1e4] and a penetration "
+                                                "extra[1] in [0, 1]");
+            if (p->poly > 0.0 && p->poly_mask != 1)
+                return fail(SANS_E_UNSUPPORTED, "raspberry: poly_mask must be 1 (the large sphere)");
+        }
         if ((p->kind == SANS_FRACTAL || p->kind == SANS_FRACTAL_CORE_SHELL)
             && !(p->extra[1] > 1.0 && p->extra[1] <= 3.0))
             return fail(SANS_E_INVALID_ARG, "fractal aggregate: dimension extra[1] must be in (1, 3]");
@@ -1583,6 +1596,10 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     if (is_sphere_family(p->kind)) {
         a.sf_n = (int32_t)p->extra[0];
         a.sf_gap = p->size[1];
+        if (p->kind == SANS_RASPBERRY) {
+            a.rb_n = (float)p->extra[0];
+            a.sf_gap = p->size[1] * (1.0 - 2.0 * p->extra[1]);
+        }
         if (p->kind == SANS_FRACTAL || p->kind == SANS_FRACTAL_CORE_SHELL) {
             const double d = p->extra[1];
             a.si_a = d * std::tgamma(d - 1.0);

@@ -32,7 +32,7 @@ EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle", "hollow_
                "vesicle", "multilayer_vesicle", "linear_pearls", "fractal", "fractal_core_shell",
                "elliptical_cylinder", "core_shell_bicelle", "core_shell_parallelepiped",
                "core_shell_bicelle_elliptical", "stacked_disks", "sc_paracrystal", "bcc_paracrystal",
-               "fcc_paracrystal", "superball", "core_shell_bicelle_elliptical_belt_rough")
+               "fcc_paracrystal", "superball", "core_shell_bicelle_elliptical_belt_rough", "raspberry")
 #: randomly oriented lamellae (weight per unit volume fraction phi)
 LAMELLAR_KINDS = ("lamellar_hg", "lamellar_stack_caille", "lamellar_hg_stack_caille", "lamellar_stack_paracrystal")
 #: shape-independent models: a cross-section in 1/cm, extra[0] = I(0)

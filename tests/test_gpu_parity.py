@@ -326,6 +326,11 @@ PER_NEUTRON = {
     "quad_belt_bicelle": (W.params(kind="core_shell_bicelle_elliptical_belt_rough", mode="quad", size=(25, 40, 0),
                                    shell=6.0, sld=(1e-6, 4e-6, 6.3e-6), extra=(5.0, 2.5e-6, 1.7, 3.0),
                                    orient_kind="isotropic", quad_n=40), 301),
+    # raspberry
+    "raspberry_poly": (W.params(kind="raspberry", size=(80.0, 15.0, 0), sld=(1e-6, 4e-6, 6.3e-6),
+                                extra=(40.0, 0.3, 0, 0), poly=0.1, poly_mask=1, phi=0.05), 30011),
+    "raspberry_py": (W.params(kind="raspberry", size=(50.0, 10.0, 0), sld=(1e-6, 4e-6, 6.3e-6),
+                              extra=(12.0, 0.0, 0, 0), sq_phi=0.15, sq_radius=62.0, phi=0.15), 30011),
 }
 
 
@@ -357,7 +362,7 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "bicelle_poly_iso", "cs_parallelepiped_gauss", "stacked_disks_gauss", "oriented_fcc_paracrystal",
              "mass_surface_fractal", "gel_fit", "sticky_coreshell", "square_well_poly_sphere",
              "oriented_superball", "lamellar_caille", "lamellar_hg", "lamellar_stack_paracrystal",
-             "belt_bicelle_gauss"]
+             "belt_bicelle_gauss", "raspberry_poly"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
