@@ -77,7 +77,8 @@ typedef struct {
                               54 head-tail bilayers in Caille stacks, 55
                               paracrystalline stacks; oriented: 56
                               elliptical bicelle with a belt and rough
-                              interfaces; 57 raspberry (isotropic)          */
+                              interfaces; 57 raspberry, 58 pearl necklace
+                              (isotropic)                                   */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -982,6 +983,40 @@ static double sphere_family_f2(const orc_params* p, const double s[3], double q)
         for (int k = 1; k < n; ++k) pairs += 2.0 * (n - k) * orc_sinc(q * k * d);
         return f * f * pairs;
     }
+    case 58: {
+        /* pearl necklace: N = extra[0] pearls (radius s0, sld[0]) joined by
+           N - 1 thin rods (length l = s1 between pearl surfaces, diameter s2,
+           sld[1]) into a freely jointed chain: each pearl-rod-pearl unit
+           points in an independent uniform direction, so the phase between
+           units d apart averages to x^d, x = sinc(q A), A = 2 R + l.  A rod
+           seen from the centre of either pearl it joins averages to beta =
+           int_R^{R+l} sinc(q s) ds / l; its own average is the thin rod's
+           P = (2/l^2) int_0^l (l - t) sinc(q t) dt.  Pair sums:
+             pearls: N + 2 sum_{d=1}^{N-1} (N - d) x^d
+             rods:   (N - 1) P + 2 beta^2 sum_{d=1}^{N-2} (N - 1 - d) x^(d-1)
+             pearl-rod (each pair once): 2 sum_{d=0}^{N-2} (N - 1 - d) x^d beta
+           weighted by the pearls' and rods' excess lengths (drho V).  The
+           integrals by 64-point Gauss-Legendre. */
+        int n = (int)p->extra[0];
+        double R = s[0], l = s[1], ms = drho * vol_sphere(R);
+        double mr = sh * ORC_PI * 0.25 * s[2] * s[2] * l;
+        double psi = orc_sph(q * R), x = orc_sinc(q * (2.0 * R + l));
+        const double *gx, *gw;
+        cap_nodes(64, &gx, &gw);
+        double beta = 0.0, prod = 0.0;
+        for (int i = 0; i < 64; ++i) {
+            double t = 0.5 * l * (gx[i] + 1.0), w = 0.5 * l * gw[i];
+            beta += w * orc_sinc(q * (R + t));
+            prod += w * (l - t) * orc_sinc(q * t);
+        }
+        beta /= l;
+        double prod_rod = 2.0 * prod / (l * l);
+        double spp = n, srr = (n - 1) * prod_rod, spr = 0.0;
+        for (int d = 1; d < n; ++d) spp += 2.0 * (n - d) * pow(x, d);
+        for (int d = 1; d <= n - 2; ++d) srr += 2.0 * beta * beta * (n - 1 - d) * pow(x, d - 1);
+        for (int d = 0; d <= n - 2; ++d) spr += 2.0 * (n - 1 - d) * pow(x, d) * beta;
+        return ms * ms * psi * psi * spp + mr * mr * srr + 2.0 * ms * mr * psi * spr;
+    }
     case 57: {
         /* raspberry: a large sphere (radius s0, sld[0]) carrying N = extra[0]
            small spheres (radius s1, sld[1]) whose centres sit at D = s0 + s1
@@ -1062,7 +1097,7 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
     if (shape_independent(p->kind)) return shape_independent_iq(p, s, q);
     if (lamellar(p->kind)) return lamellar_iq(p, s, q);
     if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
-    if ((p->kind >= 25 && p->kind <= 28) || p->kind == 57) return sphere_family_f2(p, s, q);
+    if ((p->kind >= 25 && p->kind <= 28) || p->kind == 57 || p->kind == 58) return sphere_family_f2(p, s, q);
     if (p->kind == 45) {
         /* stacked disks: N = extra[0] disks, spacing d = s1 + 2 shell along C with
            Gaussian spread extra[1]: F^2 times 1 + (2/N) sum_k (N - k) cos(k d Q_C)
@@ -1232,6 +1267,9 @@ double orc_mean_volume(const orc_params* p)
         return 4.0 / 3.0 * ORC_PI * (r * r * r * size_moment(p, 3) + 3.0 * r * r * t * size_moment(p, 2)
                                       + 3.0 * r * t * t * size_moment(p, 1) + t * t * t);
     }
+    case 58: /* pearl necklace: N pearls and N - 1 rods */
+        return p->extra[0] * vol_sphere(s[0]) * size_moment(p, (p->poly_mask & 1) ? 3 : 0)
+             + (p->extra[0] - 1.0) * ORC_PI * 0.25 * s[2] * s[2] * s[1];
     case 57: /* raspberry: the large sphere and its N small ones */
         return vol_sphere(s[0]) * size_moment(p, (p->poly_mask & 1) ? 3 : 0) + p->extra[0] * vol_sphere(s[1]);
     case 28: /* linear pearls: n spheres */

@@ -1742,3 +1742,32 @@ def test_raspberry_pair_sum(orc, q):
     if q == 0.0:
         p9 = W.params(kind="raspberry", size=(rl, rs, 0.0), sld=(sl, ss, sv), extra=(9.0, delta, 0, 0))
         assert orc.form_f2(p9, 0.0, (0.0, 0.0, 0.0)) == pytest.approx((fl + 9 * fs) ** 2, rel=1e-13)
+
+
+# ---------------------------------------------------------------- pearl necklace
+
+@pytest.mark.parametrize("q", [0.002, 0.02, 0.06])
+def test_pearl_necklace_small_chains(orc, q):
+    """One pearl is the sphere; two pearls without string contrast are a
+    rigid dumbbell, 2 + 2 sinc(qA); three, a freely jointed chain, 3 + 4x +
+    2x^2 (x = sinc(qA)); a string without pearl contrast is the thin rod,
+    2 Si(ql)/(ql) - (sin(ql/2)/(ql/2))^2; the pearl-string cross term of a
+    two-pearl necklace is 4 F_s m_r (Si(q(R+l)) - Si(qR))/(ql) (Si by SciPy)."""
+    from scipy import special
+    R, l, th = 20.0, 50.0, 4.0
+    sp, ss, sv = 1e-6, 3e-6, 6.3e-6
+    A = 2 * R + l
+    x = math.sin(q * A) / (q * A)
+    fs = _sph_amp(sp - sv, R, q)
+    mr = (ss - sv) * math.pi * th * th / 4 * l
+    neck = lambda n, sld: W.params(kind="pearl_necklace", size=(R, l, th), sld=sld, extra=(float(n), 0, 0, 0))
+    f2 = lambda pp: orc.form_f2(pp, q, (0.0, 0.0, q))
+    assert f2(neck(1, (sp, ss, sv))) == pytest.approx(fs * fs, rel=1e-13)
+    assert f2(neck(2, (sp, sv, sv))) == pytest.approx(fs * fs * (2 + 2 * x), rel=1e-12)
+    assert f2(neck(3, (sp, sv, sv))) == pytest.approx(fs * fs * (3 + 4 * x + 2 * x * x), rel=1e-12)
+    ql = q * l
+    rod = 2 * special.sici(ql)[0] / ql - (math.sin(ql / 2) / (ql / 2)) ** 2
+    assert f2(neck(2, (sv, ss, sv))) == pytest.approx(mr * mr * rod, rel=1e-10)
+    beta = (special.sici(q * (R + l))[0] - special.sici(q * R)[0]) / ql
+    full = fs * fs * (2 + 2 * x) + mr * mr * rod + 4 * fs * mr * beta
+    assert f2(neck(2, (sp, ss, sv))) == pytest.approx(full, rel=1e-10)
