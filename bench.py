@@ -91,6 +91,8 @@ STEP = {
     "sb_node":       ((32,  6,  0,  0, 0, 0), 44),  # superball, per (x, y) node: cos(Q_B R y), sin(Q_C R zm)/Q_C R
     "lam_hg_F":      ((24,  0,  0,  4, 0, 1), 30),  # head-tail bilayer: two sinc (FP64 phases), 2 pi/delta, 1/q^2
     "caille_term":   ((18,  3,  0,  6, 1, 0), 24),  # one sheet pair of a Caille stack: FP64 phase reduction, cos, exp
+    "neck_node":     ((34,  6,  0,  6, 2, 0), 44),  # necklace rod rule node: two sinc (one FP64 phase), two fma
+    "neck_unit":     ((8,   0,  0,  0, 0, 0), 12),  # necklace pair-sum step: power, three fma
     "weight":        ((3,   0,  0,  2, 0, 0), 3),   # A11
     "detector":      ((0,   5,  0, 23, 0, 1), 0),   # A12: plane crossing (quotient), pixel
     "tally":         ((0,   2,  0,  0, 0, 0), 0),   # A13: address; the add itself is a memory op
@@ -141,6 +143,9 @@ PATHS = {
                           + ["qvec"] + ["orient_angle"] * 3 + ["project_abc"] + ["sb_row"] * 24 + ["sb_node"] * 576,
     # lamellae: 30 sheets, 29 pair terms
     "lamellar_caille": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["lam_hg_F"] + ["caille_term"] * 29,
+    # pearl necklace: pearl amplitude, 24 rule nodes, 9 pair-sum steps
+    "pearl_necklace": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["sphere_F"] + ["neck_node"] * 24
+                      + ["neck_unit"] * 9,
 }
 # Exact-average paths, per quadrature node (76 x 76 = 5776 nodes per neutron),
 # all FP32:

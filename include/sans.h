@@ -219,7 +219,7 @@ typedef enum {
                                     around the core's length only; interface
                                     roughness extra[3] >= 0 (A) damps F by
                                     exp(-(q extra[3])^2 / 2)                  */
-    SANS_RASPBERRY = 57          /* isotropic: a large sphere (radius size[0],
+    SANS_RASPBERRY = 57,         /* isotropic: a large sphere (radius size[0],
                                     sld[0]) carrying extra[0] >= 0 small
                                     spheres (radius size[1], sld[1]) centred
                                     size[0] + size[1] (1 - 2 extra[1]) from
@@ -227,6 +227,14 @@ typedef enum {
                                     of penetration in small-sphere diameters),
                                     at independent uniform positions;
                                     polydispersity scales size[0] only       */
+    SANS_PEARL_NECKLACE = 58     /* isotropic: extra[0] (integer, 1..1000)
+                                    pearls of radius size[0] (sld[0]) joined
+                                    by rods of length size[1] > 0 between
+                                    pearl surfaces and diameter size[2] >= 0
+                                    (sld[1]) into a freely jointed chain; the
+                                    rods' integrals by quad_n-point
+                                    Gauss-Legendre; polydispersity scales
+                                    size[0] only                              */
 } sans_kind;
 
 /* Structure factor S(q) of the particles (when sq_phi > 0): volume fraction

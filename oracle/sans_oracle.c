@@ -996,15 +996,15 @@ static double sphere_family_f2(const orc_params* p, const double s[3], double q)
              rods:   (N - 1) P + 2 beta^2 sum_{d=1}^{N-2} (N - 1 - d) x^(d-1)
              pearl-rod (each pair once): 2 sum_{d=0}^{N-2} (N - 1 - d) x^d beta
            weighted by the pearls' and rods' excess lengths (drho V).  The
-           integrals by 64-point Gauss-Legendre. */
+           two integrals by quad_n-point Gauss-Legendre (in every mode). */
         int n = (int)p->extra[0];
         double R = s[0], l = s[1], ms = drho * vol_sphere(R);
         double mr = sh * ORC_PI * 0.25 * s[2] * s[2] * l;
         double psi = orc_sph(q * R), x = orc_sinc(q * (2.0 * R + l));
         const double *gx, *gw;
-        cap_nodes(64, &gx, &gw);
+        cap_nodes(p->quad_n, &gx, &gw);
         double beta = 0.0, prod = 0.0;
-        for (int i = 0; i < 64; ++i) {
+        for (int i = 0; i < p->quad_n; ++i) {
             double t = 0.5 * l * (gx[i] + 1.0), w = 0.5 * l * gw[i];
             beta += w * orc_sinc(q * (R + t));
             prod += w * (l - t) * orc_sinc(q * t);

@@ -141,7 +141,8 @@ struct TraceArgs {
     // sigma, count (sf_n); paracrystals: primitive vectors (A), (g D)^2 / 2
     double bi_x, sd_d, sd_sig, pc_v[3][3], pc_b;
     // belt bicelle: -sigma^2 / 2 of the interface roughness; raspberry: the
-    // number of small spheres (their centres' offset beyond R in sf_gap)
+    // number of small spheres (their centres' offset beyond R in sf_gap);
+    // pearl necklace: a rod's excess length drho pi th^2 l / 4
     double bi_rough;
     float rb_n;
     // lamellae: 2 pi / delta and the Caille parameter (the repeat distance,
@@ -569,7 +570,7 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kStackedDisks = 45, kScParacrystal = 46, kBccParacrystal = 47, kFccParacrystal = 48,
               kMassSurfaceFractal = 49, kGelFit = 50, kSuperball = 51, kLamellarHg = 52,
               kLamellarStackCaille = 53, kLamellarHgStackCaille = 54, kLamellarStackParacrystal = 55,
-              kBicelleBeltRough = 56, kRaspberry = 57 };
+              kBicelleBeltRough = 56, kRaspberry = 57, kPearlNecklace = 58 };
 
 // Randomly oriented lamellae: the weight per unit volume fraction.
 template <int KIND>
@@ -591,7 +592,7 @@ constexpr bool kShapeIndependent = (KIND >= kGuinier && KIND <= kGaussLorentzGel
 // fractal aggregates of spheres).
 template <int KIND>
 constexpr bool kSphereFamily = (KIND >= kFuzzySphere && KIND <= kLinearPearls) || KIND == kFractal
-                               || KIND == kFractalCoreShell || KIND == kRaspberry;
+                               || KIND == kFractalCoreShell || KIND == kRaspberry || KIND == kPearlNecklace;
 
 // Orientation enters the weight (the particles from the cylinder to the
 // thick hollow prism, but the micelle).
@@ -1008,6 +1009,38 @@ __device__ __forceinline__ float sphere_family_f2(const TraceArgs& a, double R, 
             sq = 1.0 + num * exp(-d * log(q * r0) - 0.5 * (d - 1.0) * log1p(1.0 / (qx * qx)));
         }
         return f * f * (float)sq;
+    } else if constexpr (KIND == kPearlNecklace) {
+        // freely jointed chain of N pearls and N - 1 rods: x = sinc(q A) per unit,
+        // beta (a rod seen from its pearls) and P (the rod itself) by the host's
+        // Gauss-Legendre rule on [0, 1] (cap_nodes: t_i, then w_i summing to 1)
+        const int n = a.sf_n, m = a.cap_n;
+        const float r = (float)R;
+        const float fs = a.contrast * k43pi * r * r * r * sph3j_d(q * R);   // a pearl's amplitude
+        const double l = a.size[1];
+        const float x = sinc_d(q * __builtin_fma(2.0, R, l));
+        const float* __restrict__ tn = a.cap_nodes;
+        const float* __restrict__ wn = a.cap_nodes + m;
+        const float ql = (float)(q * l);
+        float beta = 0.0f, prod = 0.0f;
+        for (int i = 0; i < m; ++i) {
+            beta = __builtin_fmaf(wn[i], sinc_d(__builtin_fma(l, (double)tn[i], R) * q), beta);
+            prod = __builtin_fmaf(wn[i] * (1.0f - tn[i]), sinc_f(ql * tn[i]), prod);
+        }
+        const float nf = (float)n;
+        float spp = nf, srr_sum = 0.0f, spr_sum = nf - 1.0f, xp = 1.0f;
+        for (int d = 1; d < n; ++d) {
+            const float xd = xp * x;                      // x^d
+            spp = __builtin_fmaf(2.0f * (nf - (float)d), xd, spp);
+            if (d <= n - 2) {
+                srr_sum = __builtin_fmaf(nf - 1.0f - (float)d, xp, srr_sum);   // x^(d-1)
+                spr_sum = __builtin_fmaf(nf - 1.0f - (float)d, xd, spr_sum);
+            }
+            xp = xd;
+        }
+        const float mr = a.rb_n;
+        const float srr = __builtin_fmaf(2.0f * beta * beta, srr_sum, (nf - 1.0f) * 2.0f * prod);
+        const float spr = 2.0f * beta * spr_sum;
+        return __builtin_fmaf(fs * fs, spp, __builtin_fmaf(mr * mr, srr, 2.0f * fs * mr * spr));
     } else if constexpr (KIND == kRaspberry) {
         // (F_L + N F_S c)^2 + N F_S^2 (1 - c^2), c = sinc(q D), D = R + offset:
         // the pair sum averaged over independent positions on the sphere of radius D

@@ -373,11 +373,15 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
         return mean_volume(0, size, shell, poly, mask, poly_kind, extra);
     case 39:
         return mean_volume(1, size, shell, poly, mask, poly_kind, extra);
-    case 25:
+    case 58:
+        // pearl necklace: N pearls and N - 1 rods
+        return extra[0] * c43 * size[0] * size[0] * size[0] * size_moment(poly_kind, poly, b0 ? 3 : 0)
+             + (extra[0] - 1.0) * 0.25 * kPiH * size[2] * size[2] * size[1];
     case 57:
         // raspberry: the large sphere and its small ones
         return c43 * size[0] * size[0] * size[0] * size_moment(poly_kind, poly, b0 ? 3 : 0)
              + extra[0] * c43 * size[1] * size[1] * size[1];
+    case 25:
     case 28:
         // fuzzy sphere: the sphere; linear pearls: n spheres
         return (kind == 28 ? extra[0] : 1.0) * c43 * size[0] * size[0] * size[0]

@@ -551,7 +551,8 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 54: batch_tile<54>(a, tl.first, tl.count, hist, tab); break;
         case 55: batch_tile<55>(a, tl.first, tl.count, hist, tab); break;
         case 56: batch_tile<56>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<57>(a, tl.first, tl.count, hist, tab); break;
+        case 57: batch_tile<57>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<58>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -842,6 +843,7 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(55)
         SANS_CASE(56)
         SANS_CASE(57)
+        SANS_CASE(58)
     }
 #undef SANS_CASE
     return nullptr;
@@ -914,6 +916,7 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(55)
         SANS_CASE(56)
         SANS_CASE(57)
+        SANS_CASE(58)
     }
 #undef SANS_CASE
     return nullptr;
@@ -983,6 +986,7 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(55)
         SANS_CASE(56)
         SANS_CASE(57)
+        SANS_CASE(58)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1052,6 +1056,7 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(55)
         SANS_CASE(56)
         SANS_CASE(57)
+        SANS_CASE(58)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1118,6 +1123,7 @@ PqFn pick_pq(int kind)
     case 55: return k_pq_avg<55>;
     case 56: return k_pq_avg<56>;
     case 57: return k_pq_avg<57>;
+    case 58: return k_pq_avg<58>;
     }
     return nullptr;
 }
@@ -1173,7 +1179,7 @@ bool is_shape_independent(int kind)
 bool is_sphere_family(int kind)
 {
     return (kind >= SANS_FUZZY_SPHERE && kind <= SANS_LINEAR_PEARLS) || kind == SANS_FRACTAL
-           || kind == SANS_FRACTAL_CORE_SHELL || kind == SANS_RASPBERRY;
+           || kind == SANS_FRACTAL_CORE_SHELL || kind == SANS_RASPBERRY || kind == SANS_PEARL_NECKLACE;
 }
 
 // Orientation enters the weight (the particles from the cylinder to the thick
@@ -1192,6 +1198,7 @@ size_t rule_floats(const sans_params& p)
     if (p.kind == SANS_BARBELL || p.kind == SANS_CAPPED_CYLINDER) return 3 * (size_t)p.quad_n;
     if (p.kind == SANS_SUPERBALL) return (size_t)host::superball_rule_size(p.quad_n);
     if (p.kind == SANS_LAMELLAR_STACK_CAILLE || p.kind == SANS_LAMELLAR_HG_STACK_CAILLE) return (size_t)p.extra[0];
+    if (p.kind == SANS_PEARL_NECKLACE) return 2 * (size_t)p.quad_n;
     return 0;
 }
 
@@ -1211,6 +1218,15 @@ void fill_nodes(const sans_params& p, float* out, const float* base, TraceArgs& 
         const double euler_gamma = 0.57721566490153286061;
         out[0] = 0.0f;
         for (size_t k = 1; k < nr; ++k) out[k] = (float)(euler_gamma + std::log(kPi * (double)k));
+    } else if (p.kind == SANS_PEARL_NECKLACE) {
+        // Gauss-Legendre on [0, 1]: nodes, then weights summing to 1
+        const int n = p.quad_n;
+        std::vector<double> gx(n), gw(n);
+        host::gauss_legendre(n, gx.data(), gw.data());
+        for (int i = 0; i < n; ++i) {
+            out[i] = (float)(0.5 * (gx[i] + 1.0));
+            out[n + i] = (float)(0.5 * gw[i]);
+        }
     } else if (nr) {
         host::cap_rule(p.kind == SANS_BARBELL, p.size[0], p.size[1], p.size[2], p.quad_n, out);
     }
@@ -1242,7 +1258,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 57) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 58) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -1274,7 +1290,8 @@ int validate(const sans_params* p)
                     ? 2
                     : 1;
     if (is_sphere_family(p->kind))
-        nsize = (p->kind == SANS_FRACTAL || p->kind == SANS_FRACTAL_CORE_SHELL || p->kind == SANS_RASPBERRY) ? 2 : 1;
+        nsize = (p->kind == SANS_FRACTAL || p->kind == SANS_FRACTAL_CORE_SHELL || p->kind == SANS_RASPBERRY
+                 || p->kind == SANS_PEARL_NECKLACE) ? 2 : 1;
     for (int k = 0; k < nsize; ++k)
         if (!(p->size[k] > 0.0) || !finite(p->size[k])) return fail(SANS_E_INVALID_ARG, "size must be > 0");
     if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
@@ -1410,6 +1427,15 @@ int validate(const sans_params* p)
             return fail(SANS_E_INVALID_ARG, "need a gap size[1] >= 0 and an integer count extra[0] in 1..1000");
         if (p->kind == SANS_MULTILAYER_VESICLE && p->poly > 0.0 && p->poly_mask != 0)
             return fail(SANS_E_UNSUPPORTED, "multilayer vesicle: monodisperse only");
+        if (p->kind == SANS_PEARL_NECKLACE) {
+            if (!(p->extra[0] >= 1.0 && p->extra[0] <= 1000.0 && p->extra[0] == std::floor(p->extra[0])
+                  && p->size[2] >= 0.0 && finite(p->size[2])))
+                return fail(SANS_E_INVALID_ARG, "pearl necklace: integer pearl count extra[0] in 1..1000 and a rod "
+                                                "diameter size[2] >= 0");
+            if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
+            if (p->poly > 0.0 && p->poly_mask != 1)
+                return fail(SANS_E_UNSUPPORTED, "pearl necklace: poly_mask must be 1 (the pearls)");
+        }
         if (p->kind == SANS_RASPBERRY) {
             if (!(p->extra[0] >= 0.0 && p->extra[0] <= 1e4 && p->extra[1] >= 0.0 && p->extra[1] <= 1.0))
                 return fail(SANS_E_INVALID_ARG, "raspberry: need a count extra[0] in [0, 1e4] and a penetration "
@@ -1596,6 +1622,10 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     if (is_sphere_family(p->kind)) {
         a.sf_n = (int32_t)p->extra[0];
         a.sf_gap = p->size[1];
+        if (p->kind == SANS_PEARL_NECKLACE) {
+            a.cap_n = p->quad_n;
+            a.rb_n = (float)((p->sld[1] - p->sld[2]) * kPi * 0.25 * p->size[2] * p->size[2] * p->size[1]);
+        }
         if (p->kind == SANS_RASPBERRY) {
             a.rb_n = (float)p->extra[0];
             a.sf_gap = p->size[1] * (1.0 - 2.0 * p->extra[1]);

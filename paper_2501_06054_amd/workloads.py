@@ -32,7 +32,8 @@ EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle", "hollow_
                "vesicle", "multilayer_vesicle", "linear_pearls", "fractal", "fractal_core_shell",
                "elliptical_cylinder", "core_shell_bicelle", "core_shell_parallelepiped",
                "core_shell_bicelle_elliptical", "stacked_disks", "sc_paracrystal", "bcc_paracrystal",
-               "fcc_paracrystal", "superball", "core_shell_bicelle_elliptical_belt_rough", "raspberry")
+               "fcc_paracrystal", "superball", "core_shell_bicelle_elliptical_belt_rough", "raspberry",
+               "pearl_necklace")
 #: randomly oriented lamellae (weight per unit volume fraction phi)
 LAMELLAR_KINDS = ("lamellar_hg", "lamellar_stack_caille", "lamellar_hg_stack_caille", "lamellar_stack_paracrystal")
 #: shape-independent models: a cross-section in 1/cm, extra[0] = I(0)
@@ -342,6 +343,16 @@ def lamellar_caille() -> dict:
                               extra=(30.0, 0.1, 0.0, 0.0), phi=0.1, nx=256, ny=256))
 
 
+def pearl_necklace() -> dict:
+    """Pearl necklaces: 10 pearls of radius 40 A (SLD 1e-6) joined by 60 A
+    rods 8 A thick (SLD 3e-6) into freely jointed chains, solvent 6.3e-6,
+    the rods' integrals by a 24-point rule, volume fraction 0.02, 256x256,
+    1e9 neutrons."""
+    return dict(name="pearl_necklace", n=10**9, seed=28, exp_id=0,
+                params=params(kind="pearl_necklace", size=(40.0, 60.0, 8.0), sld=(1e-6, 3e-6, 6.3e-6),
+                              extra=(10.0, 0.0, 0.0, 0.0), quad_n=24, phi=0.02, nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -369,6 +380,7 @@ WORKLOADS = {
     "mass_surface_fractal": mass_surface_fractal,
     "oriented_superball": oriented_superball,
     "lamellar_caille": lamellar_caille,
+    "pearl_necklace": pearl_necklace,
 }
 
 

@@ -331,6 +331,11 @@ PER_NEUTRON = {
                                 extra=(40.0, 0.3, 0, 0), poly=0.1, poly_mask=1, phi=0.05), 30011),
     "raspberry_py": (W.params(kind="raspberry", size=(50.0, 10.0, 0), sld=(1e-6, 4e-6, 6.3e-6),
                               extra=(12.0, 0.0, 0, 0), sq_phi=0.15, sq_radius=62.0, phi=0.15), 30011),
+    # pearl necklace
+    "pearl_necklace": (W.workload("pearl_necklace")["params"], 50021),
+    "pearl_necklace_long_poly": (W.params(kind="pearl_necklace", size=(15.0, 120.0, 5.0), sld=(2e-6, 1e-6, 6.3e-6),
+                                          extra=(60.0, 0, 0, 0), quad_n=40, poly=0.1, poly_mask=1), 30011),
+    "pearl_single": (W.params(kind="pearl_necklace", size=(30.0, 10.0, 4.0), extra=(1.0, 0, 0, 0), quad_n=8), 10011),
 }
 
 
@@ -362,7 +367,7 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "bicelle_poly_iso", "cs_parallelepiped_gauss", "stacked_disks_gauss", "oriented_fcc_paracrystal",
              "mass_surface_fractal", "gel_fit", "sticky_coreshell", "square_well_poly_sphere",
              "oriented_superball", "lamellar_caille", "lamellar_hg", "lamellar_stack_paracrystal",
-             "belt_bicelle_gauss", "raspberry_poly"]
+             "belt_bicelle_gauss", "raspberry_poly", "pearl_necklace"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -497,7 +502,8 @@ def test_full_size_coreshell(S):
 
 @pytest.mark.parametrize("name", ["oriented_cylinder", "oriented_ellipsoid", "oriented_barbell",
                                   "oriented_hollow_prism", "micelle_py", "oriented_core_shell_cylinder",
-                                  "teubner_strey", "sticky_coreshell", "mass_surface_fractal", "lamellar_caille"])
+                                  "teubner_strey", "sticky_coreshell", "mass_surface_fractal", "lamellar_caille",
+                                  "pearl_necklace"])
 def test_full_size_sampled(S, name):
     """1e9- and 1e8-neutron workloads: the full run equals the sum of its chunks, and
     windows spread over the whole index range match the oracle neutron by
