@@ -33,7 +33,7 @@ KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelep
         "mass_surface_fractal": 49, "gel_fit": 50, "superball": 51,
         "lamellar_hg": 52, "lamellar_stack_caille": 53, "lamellar_hg_stack_caille": 54,
         "lamellar_stack_paracrystal": 55, "core_shell_bicelle_elliptical_belt_rough": 56,
-        "raspberry": 57, "pearl_necklace": 58}
+        "raspberry": 57, "pearl_necklace": 58, "binary_hard_sphere": 59}
 SQ_KIND = {"hard_sphere": 0, "sticky_hard_sphere": 1, "square_well": 2}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
@@ -100,6 +100,7 @@ def lib():
         L.orc_sticky_sq.restype = d
         L.orc_square_well_sq.argtypes = [d, d, d, d, d]
         L.orc_square_well_sq.restype = d
+        L.orc_bhs_inverse_s.argtypes = [d, d, d, d, d, P(d), P(d)]
         L.orc_py_series.argtypes = [d, i32, P(d)]
         L.orc_table_normal.argtypes = [i32, P(d)]
         L.orc_table_truncnorm.argtypes = [i32, d, P(d)]
@@ -258,6 +259,14 @@ def sticky_sq(q: float, radius: float, eta: float, tau: float) -> float:
 
 def square_well_sq(q: float, radius: float, eta: float, depth: float, width: float) -> float:
     return lib().orc_square_well_sq(q, radius, eta, depth, width)
+
+
+def bhs_inverse_s(r1: float, r2: float, phi1: float, phi2: float, q: float):
+    """I - C(q) of a binary hard-sphere mixture (Percus-Yevick) as a complex 2x2 matrix."""
+    re = np.zeros(4)
+    im = np.zeros(4)
+    lib().orc_bhs_inverse_s(r1, r2, phi1, phi2, q, _ptr(re, C.c_double), _ptr(im, C.c_double))
+    return (re + 1j * im).reshape(2, 2)
 
 
 def py_series(phi: float, nterms: int) -> np.ndarray:

@@ -78,7 +78,9 @@ typedef struct {
                               paracrystalline stacks; oriented: 56
                               elliptical bicelle with a belt and rough
                               interfaces; 57 raspberry, 58 pearl necklace
-                              (isotropic)                                   */
+                              (isotropic); 59 binary hard spheres (two
+                              sizes with their Percus-Yevick partial
+                              structure factors)                            */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -1089,6 +1091,82 @@ static double lamellar_iq(const orc_params* p, const double s[3], double q)
     return 2.0 * ORC_PI / delta * f1 * f1 * st / (q * q);
 }
 
+/* Binary hard spheres (Tables I-II, group F): species 1 (radius s0,
+ * sld[0]) and 2 (radius s1, sld[1]) at volume fractions phi - extra[0] and
+ * extra[0]; number densities n_i = phi_i / V_i.  Their Percus-Yevick
+ * partial structure factors from Baxter's factorisation for mixtures:
+ * with diameters d_i, xi_m = (pi/6) sum_i n_i d_i^m and D = 1 - xi_3,
+ *   Q_ij(r) = a_i/2 (r^2 - d_ij^2) + b_i (r - d_ij) on (d_i - d_j)/2 < r < d_ij,
+ *   d_ij = (d_i + d_j)/2, a_i = (1 - xi_3 + 3 d_i xi_2)/D^2,
+ *   b_i = -(3/2) d_i^2 xi_2 / D^2,
+ *   Qhat_ij(q) = delta_ij - 2 pi sqrt(n_i n_j) int Q_ij(r) exp(i q r) dr,
+ * and I - C(q) = Qhat(q)^H Qhat(q) (C_ij = sqrt(n_i n_j) c_ij), S = (I - C)^-1.
+ * The cross-section sum_ij sqrt(n_i n_j) F_i F_j S_ij = v^T S v with
+ * v_i = sqrt(n_i) F_i; returned per unit total number density (the weight's
+ * phi / <V> is n_1 + n_2).  Integrals by composite Gauss-Legendre. */
+static void bhs_qhat(const double d[2], const double n[2], double q, double re[2][2], double im[2][2])
+{
+    double xi2 = ORC_PI / 6.0 * (n[0] * d[0] * d[0] + n[1] * d[1] * d[1]);
+    double xi3 = ORC_PI / 6.0 * (n[0] * d[0] * d[0] * d[0] + n[1] * d[1] * d[1] * d[1]);
+    double dd = 1.0 - xi3;
+    double gx[32], gw[32];
+    orc_gauss_legendre(32, gx, gw);
+    for (int i = 0; i < 2; ++i) {
+        double a = (1.0 - xi3 + 3.0 * d[i] * xi2) / (dd * dd), b = -1.5 * d[i] * d[i] * xi2 / (dd * dd);
+        for (int j = 0; j < 2; ++j) {
+            double dij = 0.5 * (d[i] + d[j]), lo = 0.5 * (d[i] - d[j]);
+            int npan = 1 + (int)(q * (dij - lo) / 2.0);
+            double h = (dij - lo) / npan, cr = 0.0, ci = 0.0;
+            for (int pnl = 0; pnl < npan; ++pnl) {
+                for (int k = 0; k < 32; ++k) {
+                    double r = lo + h * (pnl + 0.5 * (gx[k] + 1.0)), w = 0.5 * h * gw[k];
+                    double qq = 0.5 * a * (r * r - dij * dij) + b * (r - dij);
+                    cr += w * qq * cos(q * r);
+                    ci += w * qq * sin(q * r);
+                }
+            }
+            double f = 2.0 * ORC_PI * sqrt(n[i] * n[j]);
+            re[i][j] = (i == j ? 1.0 : 0.0) - f * cr;
+            im[i][j] = -f * ci;
+        }
+    }
+}
+
+/* I - C = Qhat^H Qhat, as a 2x2 complex matrix (re, im). */
+void orc_bhs_inverse_s(double r1, double r2, double phi1, double phi2, double q, double re[4], double im[4])
+{
+    double d[2] = {2.0 * r1, 2.0 * r2};
+    double n[2] = {phi1 / vol_sphere(r1), phi2 / vol_sphere(r2)};
+    double qr[2][2], qi[2][2];
+    bhs_qhat(d, n, q, qr, qi);
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            double sr = 0.0, si = 0.0;
+            for (int l = 0; l < 2; ++l) { /* conj(Q_li) Q_lj */
+                sr += qr[l][i] * qr[l][j] + qi[l][i] * qi[l][j];
+                si += qr[l][i] * qi[l][j] - qi[l][i] * qr[l][j];
+            }
+            re[2 * i + j] = sr;
+            im[2 * i + j] = si;
+        }
+}
+
+static double binary_hs_f2(const orc_params* p, const double s[3], double q)
+{
+    double phi2 = p->extra[0], phi1 = p->phi - phi2;
+    double n1 = phi1 / vol_sphere(s[0]), n2 = phi2 / vol_sphere(s[1]), nt = n1 + n2;
+    double f1 = (p->sld[0] - p->sld[2]) * vol_sphere(s[0]) * orc_sph(q * s[0]);
+    double f2 = (p->sld[1] - p->sld[2]) * vol_sphere(s[1]) * orc_sph(q * s[1]);
+    double re[4], im[4];
+    orc_bhs_inverse_s(s[0], s[1], phi1, phi2, q, re, im);
+    /* S = (I - C)^-1 is real symmetric: invert the real part (the imaginary
+       part vanishes, pinned in the tests) */
+    double det = re[0] * re[3] - re[1] * re[2];
+    double s11 = re[3] / det, s22 = re[0] / det, s12 = -re[1] / det;
+    double v1 = sqrt(n1) * f1, v2 = sqrt(n2) * f2;
+    return (v1 * v1 * s11 + 2.0 * v1 * v2 * s12 + v2 * v2 * s22) / nt;
+}
+
 /* The squared amplitude of one particle, or for the micelle its scattering
  * per particle (it has incoherent chain terms); for the shape-independent
  * models their cross-section in 1/cm. */
@@ -1096,6 +1174,7 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
 {
     if (shape_independent(p->kind)) return shape_independent_iq(p, s, q);
     if (lamellar(p->kind)) return lamellar_iq(p, s, q);
+    if (p->kind == 59) return binary_hs_f2(p, s, q);
     if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
     if ((p->kind >= 25 && p->kind <= 28) || p->kind == 57 || p->kind == 58) return sphere_family_f2(p, s, q);
     if (p->kind == 45) {
@@ -1266,6 +1345,10 @@ double orc_mean_volume(const orc_params* p)
         if (!b0) return vol_sphere(r + t);
         return 4.0 / 3.0 * ORC_PI * (r * r * r * size_moment(p, 3) + 3.0 * r * r * t * size_moment(p, 2)
                                       + 3.0 * r * t * t * size_moment(p, 1) + t * t * t);
+    }
+    case 59: { /* binary hard spheres: total volume fraction over total number density */
+        double phi2 = p->extra[0], phi1 = p->phi - phi2;
+        return p->phi / (phi1 / vol_sphere(s[0]) + phi2 / vol_sphere(s[1]));
     }
     case 58: /* pearl necklace: N pearls and N - 1 rods */
         return p->extra[0] * vol_sphere(s[0]) * size_moment(p, (p->poly_mask & 1) ? 3 : 0)

@@ -1771,3 +1771,38 @@ def test_pearl_necklace_small_chains(orc, q):
     beta = (special.sici(q * (R + l))[0] - special.sici(q * R)[0]) / ql
     full = fs * fs * (2 + 2 * x) + mr * mr * rod + 4 * fs * mr * beta
     assert f2(neck(2, (sp, ss, sv))) == pytest.approx(full, rel=1e-10)
+
+
+# ---------------------------------------------------------------- binary hard spheres
+
+@pytest.mark.parametrize("r1,r2,p1,p2", [(50.0, 20.0, 0.2, 0.1), (40.0, 10.0, 0.05, 0.3), (30.0, 27.0, 0.25, 0.2)])
+def test_binary_hard_spheres_factorisation_is_real(orc, r1, r2, p1, p2):
+    """I - C(q) = Qhat^H Qhat must come out real and symmetric (the direct
+    correlation functions are real and even): only Baxter's solution for the
+    mixture does, with both the coefficients and the order of the factors
+    right; it is positive definite."""
+    for q in (0.0, 0.004, 0.03, 0.09):
+        m = orc.bhs_inverse_s(r1, r2, p1, p2, q)
+        assert np.max(np.abs(m.imag)) <= 1e-12 * np.max(np.abs(m.real))
+        assert m[0, 1].real == pytest.approx(m[1, 0].real, rel=1e-12)
+        assert np.all(np.linalg.eigvalsh(m.real) > 0)
+
+
+@pytest.mark.parametrize("q", [0.0, 0.01, 0.04, 0.1])
+def test_binary_hard_spheres_limits(orc, q):
+    """Equal radii: the number-weighted sum of the partials is the
+    one-component Percus-Yevick S at the total volume fraction (and so is the
+    intensity for equal contrasts); no second species: the sphere with its
+    own Percus-Yevick S."""
+    R = 30.0
+    m = orc.bhs_inverse_s(R, R, 0.15, 0.1, q)
+    x = np.sqrt(np.array([0.6, 0.4]))
+    assert x @ np.linalg.inv(m.real) @ x == pytest.approx(orc.py_sq(q, R, 0.25), rel=1e-11)
+    same = W.params(kind="binary_hard_sphere", size=(R, R, 0.0), sld=(2e-6, 2e-6, 6.3e-6), phi=0.25,
+                    extra=(0.1, 0, 0, 0))
+    f = _sph_amp(2e-6 - 6.3e-6, R, q)
+    assert orc.form_f2(same, q, (0.0, 0.0, q)) == pytest.approx(f * f * orc.py_sq(q, R, 0.25), rel=1e-11)
+    one = W.params(kind="binary_hard_sphere", size=(50.0, 12.0, 0.0), sld=(1e-6, 4e-6, 6.3e-6), phi=0.2,
+                   extra=(0.0, 0, 0, 0))
+    f1 = _sph_amp(1e-6 - 6.3e-6, 50.0, q)
+    assert orc.form_f2(one, q, (0.0, 0.0, q)) == pytest.approx(f1 * f1 * orc.py_sq(q, 50.0, 0.2), rel=1e-11)
