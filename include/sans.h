@@ -227,7 +227,7 @@ typedef enum {
                                     of penetration in small-sphere diameters),
                                     at independent uniform positions;
                                     polydispersity scales size[0] only       */
-    SANS_PEARL_NECKLACE = 58     /* isotropic: extra[0] (integer, 1..1000)
+    SANS_PEARL_NECKLACE = 58,    /* isotropic: extra[0] (integer, 1..1000)
                                     pearls of radius size[0] (sld[0]) joined
                                     by rods of length size[1] > 0 between
                                     pearl surfaces and diameter size[2] >= 0
@@ -235,6 +235,14 @@ typedef enum {
                                     rods' integrals by quad_n-point
                                     Gauss-Legendre; polydispersity scales
                                     size[0] only                              */
+    SANS_BINARY_HARD_SPHERE = 59 /* isotropic: spheres of radius size[0]
+                                    (sld[0]) and size[1] (sld[1]) at volume
+                                    fractions phi - extra[0] and extra[0]
+                                    (0 <= extra[0] <= phi < 0.6), with their
+                                    Percus-Yevick partial structure factors
+                                    (Baxter's factorisation for mixtures);
+                                    monodisperse, no separate structure
+                                    factor                                    */
 } sans_kind;
 
 /* Structure factor S(q) of the particles (when sq_phi > 0): volume fraction

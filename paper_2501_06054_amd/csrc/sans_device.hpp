@@ -145,6 +145,9 @@ struct TraceArgs {
     // pearl necklace: a rod's excess length drho pi th^2 l / 4
     double bi_rough;
     float rb_n;
+    // binary hard spheres: sqrt(n_1), sqrt(n_2) and 1 / (n_1 + n_2) (number
+    // densities in 1/A^3, the nodes of Baxter's integrals in cap_nodes)
+    float bhs_sn[2], bhs_int;
     // lamellae: 2 pi / delta and the Caille parameter (the repeat distance,
     // spacing spread and count in sd_d, sd_sig, sf_n; the Caille exponents'
     // gamma + ln(pi n) in cap_nodes)
@@ -570,7 +573,7 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kStackedDisks = 45, kScParacrystal = 46, kBccParacrystal = 47, kFccParacrystal = 48,
               kMassSurfaceFractal = 49, kGelFit = 50, kSuperball = 51, kLamellarHg = 52,
               kLamellarStackCaille = 53, kLamellarHgStackCaille = 54, kLamellarStackParacrystal = 55,
-              kBicelleBeltRough = 56, kRaspberry = 57, kPearlNecklace = 58 };
+              kBicelleBeltRough = 56, kRaspberry = 57, kPearlNecklace = 58, kBinaryHardSphere = 59 };
 
 // Randomly oriented lamellae: the weight per unit volume fraction.
 template <int KIND>
@@ -592,7 +595,8 @@ constexpr bool kShapeIndependent = (KIND >= kGuinier && KIND <= kGaussLorentzGel
 // fractal aggregates of spheres).
 template <int KIND>
 constexpr bool kSphereFamily = (KIND >= kFuzzySphere && KIND <= kLinearPearls) || KIND == kFractal
-                               || KIND == kFractalCoreShell || KIND == kRaspberry || KIND == kPearlNecklace;
+                               || KIND == kFractalCoreShell || KIND == kRaspberry || KIND == kPearlNecklace
+                               || KIND == kBinaryHardSphere;
 
 // Orientation enters the weight (the particles from the cylinder to the
 // thick hollow prism, but the micelle).
@@ -1041,6 +1045,37 @@ __device__ __forceinline__ float sphere_family_f2(const TraceArgs& a, double R, 
         const float srr = __builtin_fmaf(2.0f * beta * beta, srr_sum, (nf - 1.0f) * 2.0f * prod);
         const float spr = 2.0f * beta * spr_sum;
         return __builtin_fmaf(fs * fs, spp, __builtin_fmaf(mr * mr, srr, 2.0f * fs * mr * spr));
+    } else if constexpr (KIND == kBinaryHardSphere) {
+        // Qhat_ij = delta_ij - sum_k W_k exp(i q r_k) over the host's rule
+        // (cap_nodes: per (i, j) in row order 16 r_k, then 16 W_k, the factor
+        // 2 pi sqrt(n_i n_j) Q_ij(r_k) and the weight folded into W_k); I - C =
+        // Qhat^H Qhat (real), S its inverse; v^T S v / (n_1 + n_2), v_i = sqrt(n_i) F_i
+        const float* __restrict__ nd = a.cap_nodes;
+        const float qf = (float)q;
+        float qr[4], qi[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float cr = 0.0f, ci = 0.0f;
+#pragma unroll 4
+            for (int k = 0; k < 16; ++k) {
+                float sv, cv;
+                sincos_f(qf * nd[32 * e + k], sv, cv);
+                const float w = nd[32 * e + 16 + k];
+                cr = __builtin_fmaf(w, cv, cr);
+                ci = __builtin_fmaf(w, sv, ci);
+            }
+            qr[e] = ((e == 0 || e == 3) ? 1.0f : 0.0f) - cr;
+            qi[e] = -ci;
+        }
+        const float m00 = qr[0] * qr[0] + qi[0] * qi[0] + qr[2] * qr[2] + qi[2] * qi[2];
+        const float m11 = qr[1] * qr[1] + qi[1] * qi[1] + qr[3] * qr[3] + qi[3] * qi[3];
+        const float m01 = qr[0] * qr[1] + qi[0] * qi[1] + qr[2] * qr[3] + qi[2] * qi[3];
+        const float idet = rcpf(__builtin_fmaf(m00, m11, -m01 * m01));
+        const float r1 = (float)R, r2 = (float)a.size[1];
+        const float v1 = a.bhs_sn[0] * a.contrast * k43pi * r1 * r1 * r1 * sph3j_d(q * R);
+        const float v2 = a.bhs_sn[1] * a.cs_shell * k43pi * r2 * r2 * r2 * sph3j_d(q * a.size[1]);
+        const float quad = __builtin_fmaf(v1 * v1, m11, __builtin_fmaf(-2.0f * v1 * v2, m01, v2 * v2 * m00));
+        return quad * idet * a.bhs_int;
     } else if constexpr (KIND == kRaspberry) {
         // (F_L + N F_S c)^2 + N F_S^2 (1 - c^2), c = sinc(q D), D = R + offset:
         // the pair sum averaged over independent positions on the sphere of radius D

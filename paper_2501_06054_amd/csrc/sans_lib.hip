@@ -552,7 +552,8 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 55: batch_tile<55>(a, tl.first, tl.count, hist, tab); break;
         case 56: batch_tile<56>(a, tl.first, tl.count, hist, tab); break;
         case 57: batch_tile<57>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<58>(a, tl.first, tl.count, hist, tab); break;
+        case 58: batch_tile<58>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<59>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -844,6 +845,7 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(56)
         SANS_CASE(57)
         SANS_CASE(58)
+        SANS_CASE(59)
     }
 #undef SANS_CASE
     return nullptr;
@@ -917,6 +919,7 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(56)
         SANS_CASE(57)
         SANS_CASE(58)
+        SANS_CASE(59)
     }
 #undef SANS_CASE
     return nullptr;
@@ -987,6 +990,7 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(56)
         SANS_CASE(57)
         SANS_CASE(58)
+        SANS_CASE(59)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1057,6 +1061,7 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(56)
         SANS_CASE(57)
         SANS_CASE(58)
+        SANS_CASE(59)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1124,6 +1129,7 @@ PqFn pick_pq(int kind)
     case 56: return k_pq_avg<56>;
     case 57: return k_pq_avg<57>;
     case 58: return k_pq_avg<58>;
+    case 59: return k_pq_avg<59>;
     }
     return nullptr;
 }
@@ -1179,7 +1185,8 @@ bool is_shape_independent(int kind)
 bool is_sphere_family(int kind)
 {
     return (kind >= SANS_FUZZY_SPHERE && kind <= SANS_LINEAR_PEARLS) || kind == SANS_FRACTAL
-           || kind == SANS_FRACTAL_CORE_SHELL || kind == SANS_RASPBERRY || kind == SANS_PEARL_NECKLACE;
+           || kind == SANS_FRACTAL_CORE_SHELL || kind == SANS_RASPBERRY || kind == SANS_PEARL_NECKLACE
+           || kind == SANS_BINARY_HARD_SPHERE;
 }
 
 // Orientation enters the weight (the particles from the cylinder to the thick
@@ -1199,6 +1206,7 @@ size_t rule_floats(const sans_params& p)
     if (p.kind == SANS_SUPERBALL) return (size_t)host::superball_rule_size(p.quad_n);
     if (p.kind == SANS_LAMELLAR_STACK_CAILLE || p.kind == SANS_LAMELLAR_HG_STACK_CAILLE) return (size_t)p.extra[0];
     if (p.kind == SANS_PEARL_NECKLACE) return 2 * (size_t)p.quad_n;
+    if (p.kind == SANS_BINARY_HARD_SPHERE) return 4 * 32;
     return 0;
 }
 
@@ -1218,6 +1226,32 @@ void fill_nodes(const sans_params& p, float* out, const float* base, TraceArgs& 
         const double euler_gamma = 0.57721566490153286061;
         out[0] = 0.0f;
         for (size_t k = 1; k < nr; ++k) out[k] = (float)(euler_gamma + std::log(kPi * (double)k));
+    } else if (p.kind == SANS_BINARY_HARD_SPHERE) {
+        // Baxter's factor functions for the mixture, Q_ij(r) = a_i/2 (r^2 - d_ij^2)
+        // + b_i (r - d_ij) on (d_i - d_j)/2 < r < d_ij: 16 Gauss-Legendre nodes
+        // per (i, j), weights times 2 pi sqrt(n_i n_j) Q_ij(r_k)
+        const double d[2] = {2.0 * p.size[0], 2.0 * p.size[1]};
+        const double v1 = 4.0 / 3.0 * kPi * p.size[0] * p.size[0] * p.size[0];
+        const double v2 = 4.0 / 3.0 * kPi * p.size[1] * p.size[1] * p.size[1];
+        const double n[2] = {(p.phi - p.extra[0]) / v1, p.extra[0] / v2};
+        const double xi2 = kPi / 6.0 * (n[0] * d[0] * d[0] + n[1] * d[1] * d[1]);
+        const double xi3 = kPi / 6.0 * (n[0] * d[0] * d[0] * d[0] + n[1] * d[1] * d[1] * d[1]);
+        const double dd = 1.0 - xi3;
+        double gx[16], gw[16];
+        host::gauss_legendre(16, gx, gw);
+        for (int i = 0; i < 2; ++i) {
+            const double ai = (1.0 - xi3 + 3.0 * d[i] * xi2) / (dd * dd), bi = -1.5 * d[i] * d[i] * xi2 / (dd * dd);
+            for (int j = 0; j < 2; ++j) {
+                const double dij = 0.5 * (d[i] + d[j]), lo = 0.5 * (d[i] - d[j]), h = 0.5 * (dij - lo);
+                const double f = 2.0 * kPi * std::sqrt(n[i] * n[j]);
+                float* blk = out + 32 * (2 * i + j);
+                for (int k = 0; k < 16; ++k) {
+                    const double r = lo + h * (gx[k] + 1.0);
+                    blk[k] = (float)r;
+                    blk[16 + k] = (float)(f * h * gw[k] * (0.5 * ai * (r * r - dij * dij) + bi * (r - dij)));
+                }
+            }
+        }
     } else if (p.kind == SANS_PEARL_NECKLACE) {
         // Gauss-Legendre on [0, 1]: nodes, then weights summing to 1
         const int n = p.quad_n;
@@ -1258,7 +1292,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 58) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 59) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -1291,7 +1325,7 @@ int validate(const sans_params* p)
                     : 1;
     if (is_sphere_family(p->kind))
         nsize = (p->kind == SANS_FRACTAL || p->kind == SANS_FRACTAL_CORE_SHELL || p->kind == SANS_RASPBERRY
-                 || p->kind == SANS_PEARL_NECKLACE) ? 2 : 1;
+                 || p->kind == SANS_PEARL_NECKLACE || p->kind == SANS_BINARY_HARD_SPHERE) ? 2 : 1;
     for (int k = 0; k < nsize; ++k)
         if (!(p->size[k] > 0.0) || !finite(p->size[k])) return fail(SANS_E_INVALID_ARG, "size must be > 0");
     if (p->kind == SANS_BARBELL || p->kind == SANS_CAPPED_CYLINDER) {
@@ -1427,6 +1461,13 @@ int validate(const sans_params* p)
             return fail(SANS_E_INVALID_ARG, "need a gap size[1] >= 0 and an integer count extra[0] in 1..1000");
         if (p->kind == SANS_MULTILAYER_VESICLE && p->poly > 0.0 && p->poly_mask != 0)
             return fail(SANS_E_UNSUPPORTED, "multilayer vesicle: monodisperse only");
+        if (p->kind == SANS_BINARY_HARD_SPHERE) {
+            if (!(p->phi > 0.0 && p->phi < 0.6 && p->extra[0] >= 0.0 && p->extra[0] <= p->phi))
+                return fail(SANS_E_INVALID_ARG, "binary hard spheres: need 0 < phi < 0.6 and 0 <= extra[0] <= phi");
+            if (p->poly > 0.0) return fail(SANS_E_UNSUPPORTED, "binary hard spheres: monodisperse only");
+            if (p->sq_phi > 0.0)
+                return fail(SANS_E_UNSUPPORTED, "binary hard spheres: the partial structure factors are built in");
+        }
         if (p->kind == SANS_PEARL_NECKLACE) {
             if (!(p->extra[0] >= 1.0 && p->extra[0] <= 1000.0 && p->extra[0] == std::floor(p->extra[0])
                   && p->size[2] >= 0.0 && finite(p->size[2])))
@@ -1606,6 +1647,16 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     a.nx = p->nx;
     a.ny = p->ny;
     *mean_v = host::mean_volume(p->kind, p->size, p->shell, p->poly, p->poly_mask, p->poly_kind, p->extra);
+    if (p->kind == SANS_BINARY_HARD_SPHERE) {
+        // the total volume fraction over the total number density
+        const double v1 = 4.0 / 3.0 * kPi * p->size[0] * p->size[0] * p->size[0];
+        const double v2 = 4.0 / 3.0 * kPi * p->size[1] * p->size[1] * p->size[1];
+        const double n1 = (p->phi - p->extra[0]) / v1, n2 = p->extra[0] / v2;
+        *mean_v = p->phi / (n1 + n2);
+        a.bhs_sn[0] = (float)std::sqrt(n1);
+        a.bhs_sn[1] = (float)std::sqrt(n2);
+        a.bhs_int = (float)(1.0 / (n1 + n2));
+    }
     const double dOmega = 2.0 * 3.141592653589793 * *omc;
     // n F^2 in 1/Angstrom; a shape-independent model's cross-section is in 1/cm
     *wscale = 1e10 * dOmega * (is_shape_independent(p->kind) ? 1e-8 : p->phi / *mean_v);

@@ -336,6 +336,11 @@ PER_NEUTRON = {
     "pearl_necklace_long_poly": (W.params(kind="pearl_necklace", size=(15.0, 120.0, 5.0), sld=(2e-6, 1e-6, 6.3e-6),
                                           extra=(60.0, 0, 0, 0), quad_n=40, poly=0.1, poly_mask=1), 30011),
     "pearl_single": (W.params(kind="pearl_necklace", size=(30.0, 10.0, 4.0), extra=(1.0, 0, 0, 0), quad_n=8), 10011),
+    # binary hard spheres
+    "binary_hard_sphere": (W.params(kind="binary_hard_sphere", size=(50.0, 20.0, 0), sld=(1e-6, 4e-6, 6.3e-6),
+                                    phi=0.3, extra=(0.1, 0, 0, 0)), 30011),
+    "binary_hard_sphere_dilute_small": (W.params(kind="binary_hard_sphere", size=(80.0, 12.0, 0),
+                                                 sld=(3e-6, 0.5e-6, 6.3e-6), phi=0.25, extra=(0.01, 0, 0, 0)), 30011),
 }
 
 
@@ -367,7 +372,7 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "bicelle_poly_iso", "cs_parallelepiped_gauss", "stacked_disks_gauss", "oriented_fcc_paracrystal",
              "mass_surface_fractal", "gel_fit", "sticky_coreshell", "square_well_poly_sphere",
              "oriented_superball", "lamellar_caille", "lamellar_hg", "lamellar_stack_paracrystal",
-             "belt_bicelle_gauss", "raspberry_poly", "pearl_necklace"]
+             "belt_bicelle_gauss", "raspberry_poly", "pearl_necklace", "binary_hard_sphere"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
