@@ -80,7 +80,8 @@ typedef struct {
                               interfaces; 57 raspberry, 58 pearl necklace
                               (isotropic); 59 binary hard spheres (two
                               sizes with their Percus-Yevick partial
-                              structure factors)                            */
+                              structure factors); 60 adsorbed layers on
+                              large particles                               */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -1049,7 +1050,7 @@ static double sphere_family_f2(const orc_params* p, const double s[3], double q)
  * S the stacking factor per sheet (1 for isolated sheets).  Profiles are
  * symmetric: F1(q) = int drho(z) cos(q z) dz.  Here f2 is returned per unit
  * phi (the weight's phi / <V> with <V> = 1). */
-static int lamellar(int kind) { return kind >= 52 && kind <= 55; }
+static int lamellar(int kind) { return (kind >= 52 && kind <= 55) || kind == 60; }
 
 /* Caille stacking of N sheets, repeat distance d, Caille parameter eta: the
  * mean-square displacement of sheets n apart grows as (eta d^2 / 2 pi^2)
@@ -1068,6 +1069,15 @@ static double lamellar_iq(const orc_params* p, const double s[3], double q)
 {
     double rt = p->sld[0] - p->sld[2], rh = p->sld[1] - p->sld[2];
     double f1, delta, st = 1.0;
+    if (p->kind == 60) {
+        /* a layer adsorbed on large particles (radius R = s0, contrast-matched
+           cores; volume fraction phi): locally a flat sheet of excess
+           thickness t = shell (the adsorbed amount over the layer's bulk
+           density) with 3 phi / R of area per volume, smeared by a Gaussian of
+           width sigma = extra[0]: phi (3 / R) 2 pi (drho t)^2 exp(-(q sigma)^2) / q^2 */
+        double t = p->shell, sg = p->extra[0];
+        return 3.0 / s[0] * 2.0 * ORC_PI * (rt * t) * (rt * t) * exp(-q * q * sg * sg) / (q * q);
+    }
     if (p->kind == 52 || p->kind == 54) {
         /* tails over |z| < L_T (sld[0]), heads over L_T < |z| < L_T + L_H (sld[1]) */
         double lt = s[0], lh = s[1];
@@ -1321,7 +1331,7 @@ double orc_mean_volume(const orc_params* p)
              * size_moment(p, p->poly_mask == 7 ? 3 : 0);
     case 51:
         return superball_volume(s[0], p->extra[0]) * size_moment(p, b0 ? 3 : 0);
-    case 52: case 53: case 54: case 55: /* lamellae: f2 is per unit volume fraction */
+    case 52: case 53: case 54: case 55: case 60: /* lamellae, adsorbed layers: f2 is per unit volume fraction */
         return 1.0;
     case 25: /* fuzzy sphere: the sphere's volume */
         return vol_sphere(s[0]) * size_moment(p, b0 ? 3 : 0);

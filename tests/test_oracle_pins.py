@@ -1806,3 +1806,31 @@ def test_binary_hard_spheres_limits(orc, q):
                    extra=(0.0, 0, 0, 0))
     f1 = _sph_amp(1e-6 - 6.3e-6, 50.0, q)
     assert orc.form_f2(one, q, (0.0, 0.0, q)) == pytest.approx(f1 * f1 * orc.py_sq(q, 50.0, 0.2), rel=1e-11)
+
+
+# ---------------------------------------------------------------- adsorbed layer
+
+def test_adsorbed_layer_is_the_thin_shell_averaged_over_its_fringes(orc):
+    """A thin shell (the vesicle of thickness t on a large core of radius R)
+    averaged over many of its fringes at qR >> 1 scatters 6 pi phi (drho t)^2
+    / (R q^2): the adsorbed layer without smearing; smearing by sigma
+    multiplies by exp(-(q sigma)^2)."""
+    from scipy import integrate
+    R, t, phi = 2000.0, 2.0, 0.05
+    sl, sv = 1.5e-6, 6.3e-6
+    ves = W.params(kind="vesicle", size=(R, 0.0, 0.0), shell=t, sld=(sv, sl, sv), phi=phi)
+    lay = W.params(kind="adsorbed_layer", size=(R, 0.0, 0.0), shell=t, sld=(sl, 0.0, sv), phi=phi)
+    lay_s = W.params(kind="adsorbed_layer", size=(R, 0.0, 0.0), shell=t, sld=(sl, 0.0, sv), phi=phi,
+                     extra=(15.0, 0, 0, 0))
+    for q in (0.02, 0.05):
+        width = 40 * math.pi / R                     # 20 fringes of sin^2(qR)
+        # the same particles: n = phi_cores / V_core, so n <F^2> = phi_cores <F^2> / V_core
+        vcore = 4 / 3 * math.pi * R ** 3
+        avg, _ = integrate.quad(lambda x: x * x * orc.form_f2(ves, x, (0.0, 0.0, x)) / vcore, q - width / 2,
+                                q + width / 2, limit=2000, epsabs=0, epsrel=1e-10)
+        avg /= width
+        # the layer's cross-section per unit volume fraction of cores is its f2
+        want = q * q * orc.form_f2(lay, q, (0.0, 0.0, q))
+        assert avg == pytest.approx(want, rel=2e-2)
+        assert orc.form_f2(lay_s, q, (0.0, 0.0, q)) == pytest.approx(
+            orc.form_f2(lay, q, (0.0, 0.0, q)) * math.exp(-(q * 15.0) ** 2), rel=1e-13)
