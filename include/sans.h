@@ -235,7 +235,7 @@ typedef enum {
                                     rods' integrals by quad_n-point
                                     Gauss-Legendre; polydispersity scales
                                     size[0] only                              */
-    SANS_BINARY_HARD_SPHERE = 59 /* isotropic: spheres of radius size[0]
+    SANS_BINARY_HARD_SPHERE = 59, /* isotropic: spheres of radius size[0]
                                     (sld[0]) and size[1] (sld[1]) at volume
                                     fractions phi - extra[0] and extra[0]
                                     (0 <= extra[0] <= phi < 0.6), with their
@@ -243,6 +243,15 @@ typedef enum {
                                     (Baxter's factorisation for mixtures);
                                     monodisperse, no separate structure
                                     factor                                    */
+    SANS_ADSORBED_LAYER = 60     /* a layer of excess thickness shell > 0
+                                    (adsorbed amount over its bulk density;
+                                    SLD sld[0]) on large contrast-matched
+                                    particles of radius size[0] at volume
+                                    fraction phi, locally flat (3 phi / R of
+                                    sheet per volume), smeared by extra[0] >= 0
+                                    (A): phi (3/R) 2 pi (drho shell)^2
+                                    exp(-(q extra[0])^2) / q^2; monodisperse,
+                                    no structure factor                       */
 } sans_kind;
 
 /* Structure factor S(q) of the particles (when sq_phi > 0): volume fraction

@@ -573,11 +573,12 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kStackedDisks = 45, kScParacrystal = 46, kBccParacrystal = 47, kFccParacrystal = 48,
               kMassSurfaceFractal = 49, kGelFit = 50, kSuperball = 51, kLamellarHg = 52,
               kLamellarStackCaille = 53, kLamellarHgStackCaille = 54, kLamellarStackParacrystal = 55,
-              kBicelleBeltRough = 56, kRaspberry = 57, kPearlNecklace = 58, kBinaryHardSphere = 59 };
+              kBicelleBeltRough = 56, kRaspberry = 57, kPearlNecklace = 58, kBinaryHardSphere = 59,
+              kAdsorbedLayer = 60 };
 
 // Randomly oriented lamellae: the weight per unit volume fraction.
 template <int KIND>
-constexpr bool kLamellar = KIND >= kLamellarHg && KIND <= kLamellarStackParacrystal;
+constexpr bool kLamellar = (KIND >= kLamellarHg && KIND <= kLamellarStackParacrystal) || KIND == kAdsorbedLayer;
 
 // F^2 multiplied by an orientation-dependent interference factor (stacked
 // disks, paracrystals).
@@ -923,6 +924,13 @@ __device__ __forceinline__ float shape_iq(const TraceArgs& a, double len, double
 template <int KIND>
 __device__ __forceinline__ float lamellar_f2(const TraceArgs& a, double q)
 {
+    if constexpr (KIND == kAdsorbedLayer) {
+        // a layer of excess thickness t on large particles, locally flat: 3 phi / R
+        // of sheet per volume (in lam_c = 6 pi / R), smeared by sigma (sd_sig)
+        const float f1 = a.contrast * a.fshell;
+        const float iq = (float)(1.0 / q);
+        return a.lam_c * f1 * f1 * __expf(-(float)(q * q * a.sd_sig * a.sd_sig)) * iq * iq;
+    }
     float f1;
     if constexpr (KIND == kLamellarHg || KIND == kLamellarHgStackCaille) {
         const double lt = a.size[0], lo = a.size[0] + a.size[1];

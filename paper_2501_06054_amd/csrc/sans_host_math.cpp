@@ -408,8 +408,8 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
         return 1.0;  // shape-independent: no particles (the weight uses the cross-section)
     case 51:
         return superball_volume(size[0], extra[0]) * size_moment(poly_kind, poly, b0 ? 3 : 0);
-    case 52: case 53: case 54: case 55:
-        return 1.0;  // lamellae: the weight is per unit volume fraction
+    case 52: case 53: case 54: case 55: case 60:
+        return 1.0;  // lamellae, adsorbed layers: the weight is per unit volume fraction
     case 12: {
         // the box minus its cavity (monodisperse)
         const double t2 = 2.0 * shell;

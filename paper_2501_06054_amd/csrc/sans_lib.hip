@@ -553,7 +553,8 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 56: batch_tile<56>(a, tl.first, tl.count, hist, tab); break;
         case 57: batch_tile<57>(a, tl.first, tl.count, hist, tab); break;
         case 58: batch_tile<58>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<59>(a, tl.first, tl.count, hist, tab); break;
+        case 59: batch_tile<59>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<60>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -846,6 +847,7 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(57)
         SANS_CASE(58)
         SANS_CASE(59)
+        SANS_CASE(60)
     }
 #undef SANS_CASE
     return nullptr;
@@ -920,6 +922,7 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(57)
         SANS_CASE(58)
         SANS_CASE(59)
+        SANS_CASE(60)
     }
 #undef SANS_CASE
     return nullptr;
@@ -991,6 +994,7 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(57)
         SANS_CASE(58)
         SANS_CASE(59)
+        SANS_CASE(60)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1062,6 +1066,7 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(57)
         SANS_CASE(58)
         SANS_CASE(59)
+        SANS_CASE(60)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1130,6 +1135,7 @@ PqFn pick_pq(int kind)
     case 57: return k_pq_avg<57>;
     case 58: return k_pq_avg<58>;
     case 59: return k_pq_avg<59>;
+    case 60: return k_pq_avg<60>;
     }
     return nullptr;
 }
@@ -1292,7 +1298,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 59) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 60) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -1313,7 +1319,7 @@ int validate(const sans_params* p)
                            || p->kind == SANS_LAMELLAR_HG || p->kind == SANS_LAMELLAR_STACK_CAILLE
                            || p->kind == SANS_LAMELLAR_STACK_PARACRYSTAL
                            || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH;
-    int nsize = (p->kind <= 1 || p->kind == SANS_SUPERBALL) ? 1 : (two_sizes ? 2 : 3);
+    int nsize = (p->kind <= 1 || p->kind == SANS_SUPERBALL || p->kind == SANS_ADSORBED_LAYER) ? 1 : (two_sizes ? 2 : 3);
     if (is_shape_independent(p->kind))
         nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK
                  || p->kind == SANS_TWO_POWER_LAW || p->kind == SANS_SPINODAL || p->kind == SANS_POROD
@@ -1334,6 +1340,12 @@ int validate(const sans_params* p)
         if (p->poly > 0.0 && p->poly_mask != 7)
             return fail(SANS_E_UNSUPPORTED, "barbell / capped cylinder: poly_mask must be 7 (all sizes)");
         if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
+    }
+    if (p->kind == SANS_ADSORBED_LAYER) {
+        if (!(p->shell > 0.0 && finite(p->shell) && p->extra[0] >= 0.0 && finite(p->extra[0])))
+            return fail(SANS_E_INVALID_ARG, "adsorbed layer: need a thickness shell > 0 and a smearing extra[0] >= 0");
+        if (p->poly > 0.0) return fail(SANS_E_UNSUPPORTED, "adsorbed layer: monodisperse only");
+        if (p->sq_phi > 0.0) return fail(SANS_E_UNSUPPORTED, "adsorbed layer: no structure factor");
     }
     if (p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH
         && !(p->shell >= 0.0 && finite(p->shell) && p->extra[0] >= 0.0 && finite(p->extra[0]) && finite(p->extra[1])
@@ -1819,6 +1831,10 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
         a.mic_d = p->extra[3];
     }
     if (p->kind == SANS_SUPERBALL) a.cap_n = p->quad_n;
+    if (p->kind == SANS_ADSORBED_LAYER) {
+        a.lam_c = (float)(6.0 * kPi / p->size[0]);
+        a.sd_sig = p->extra[0];
+    }
     if (p->kind >= SANS_LAMELLAR_HG && p->kind <= SANS_LAMELLAR_STACK_PARACRYSTAL) {
         const bool hg = p->kind == SANS_LAMELLAR_HG || p->kind == SANS_LAMELLAR_HG_STACK_CAILLE;
         const double delta = hg ? 2.0 * (p->size[0] + p->size[1]) : p->size[0];

@@ -341,6 +341,8 @@ PER_NEUTRON = {
                                     phi=0.3, extra=(0.1, 0, 0, 0)), 30011),
     "binary_hard_sphere_dilute_small": (W.params(kind="binary_hard_sphere", size=(80.0, 12.0, 0),
                                                  sld=(3e-6, 0.5e-6, 6.3e-6), phi=0.25, extra=(0.01, 0, 0, 0)), 30011),
+    "adsorbed_layer": (W.params(kind="adsorbed_layer", size=(2000.0, 0, 0), shell=2.5, sld=(1.5e-6, 0, 6.3e-6),
+                                extra=(12.0, 0, 0, 0), phi=0.05), 30011),
 }
 
 
@@ -372,7 +374,8 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "bicelle_poly_iso", "cs_parallelepiped_gauss", "stacked_disks_gauss", "oriented_fcc_paracrystal",
              "mass_surface_fractal", "gel_fit", "sticky_coreshell", "square_well_poly_sphere",
              "oriented_superball", "lamellar_caille", "lamellar_hg", "lamellar_stack_paracrystal",
-             "belt_bicelle_gauss", "raspberry_poly", "pearl_necklace", "binary_hard_sphere"]
+             "belt_bicelle_gauss", "raspberry_poly", "pearl_necklace", "binary_hard_sphere",
+             "adsorbed_layer"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
