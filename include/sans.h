@@ -436,6 +436,14 @@ int sans_debug_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t n_bloc
  * SANS_E_UNSUPPORTED if the handle has no such table. */
 int sans_debug_table(sans_model_t m, int32_t which, double* out, int32_t n);
 
+/* Host only (no device work, usable without a GPU): validates p as
+ * sans_model_create does and returns the number-averaged particle volume
+ * <V> (A^3; 1 for models whose weight is a cross-section or per unit volume
+ * fraction; the binary mixture's total volume fraction over its total number
+ * density) and the weight's scale per metre of path, 1e10 dOmega phi / <V>
+ * (1e2 dOmega for the shape-independent models).  Either output may be NULL. */
+int sans_debug_weight_scale(const sans_params* p, double* mean_volume, double* wscale);
+
 /* Traces n_exp independent virtual experiments (the paper's high-throughput
  * use: many models, parameters and neutron counts; Introduction and
  * Conclusion) in one persistent launch.  Experiment e traces neutrons

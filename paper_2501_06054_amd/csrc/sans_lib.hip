@@ -2486,6 +2486,18 @@ int sans_debug_valu_rates(double* rates, void* stream)
     return SANS_OK;
 }
 
+int sans_debug_weight_scale(const sans_params* p, double* mean_volume, double* wscale)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    TraceArgs a;
+    double mv = 0.0, ws = 0.0, omc = 0.0;
+    fill_constants(p, a, &mv, &ws, &omc);
+    if (mean_volume) *mean_volume = mv;
+    if (wscale) *wscale = ws;
+    return SANS_OK;
+}
+
 int sans_debug_table(sans_model_t m, int32_t which, double* out, int32_t n)
 {
     if (!m || !out) return fail(SANS_E_INVALID_ARG, "NULL argument");

@@ -87,6 +87,7 @@ def _load():
     L.sans_debug_trace.argtypes = [vp, u64, u64, u64, u32, vp, vp, vp, vp]
     L.sans_debug_philox.argtypes = [u64, u64, u64, u32, u32, vp, vp]
     L.sans_debug_table.argtypes = [vp, i32, P(C.c_double), i32]
+    L.sans_debug_weight_scale.argtypes = [P(sans_params), P(C.c_double), P(C.c_double)]
     L.sans_pq_avg.argtypes = [vp, vp, vp, i64, vp, vp]
     L.sans_model_constants.argtypes = [vp, P(C.c_double)]
     L.sans_trace_batch.argtypes = [C.c_int, P(sans_params), P(u64), P(u64), vp, C.c_char_p, vp]
@@ -115,7 +116,7 @@ def _load():
     L.sans_status_string.restype = C.c_char_p
     L.sans_last_error.restype = C.c_char_p
     for f in ("sans_model_create", "sans_model_destroy", "sans_trace", "sans_trace_ex",
-              "sans_debug_trace", "sans_debug_philox", "sans_debug_table", "sans_pq_avg",
+              "sans_debug_trace", "sans_debug_philox", "sans_debug_table", "sans_debug_weight_scale", "sans_pq_avg",
               "sans_model_constants", "sans_trace_batch", "sans_batch_release"):
         getattr(L, f).restype = C.c_int
     return L
@@ -220,6 +221,14 @@ def sans_debug_philox(seed: int, first: int, n: int, n_blocks: int, exp_id: int,
                       stream=None) -> None:
     _check(lib.sans_debug_philox(seed, first, n, n_blocks, exp_id, _dev(out, torch.int32, "out"),
                                  _stream(stream)), "sans_debug_philox")
+
+
+def sans_debug_weight_scale(params):
+    """(<V>, weight scale per metre) of a parameter set, computed on the host."""
+    sp = params if isinstance(params, sans_params) else to_params(params)
+    mv, ws = C.c_double(), C.c_double()
+    _check(lib.sans_debug_weight_scale(C.byref(sp), C.byref(mv), C.byref(ws)), "sans_debug_weight_scale")
+    return mv.value, ws.value
 
 
 def sans_debug_table(h, which: int, n: int):
