@@ -81,7 +81,8 @@ typedef struct {
                               (isotropic); 59 binary hard spheres (two
                               sizes with their Percus-Yevick partial
                               structure factors); 60 adsorbed layers on
-                              large particles                               */
+                              large particles; oriented: 61 pringle (a
+                              saddle-shaped plate)                          */
     int32_t mode;          /* 0 Monte Carlo draws, 1 exact quadrature average */
     double size[3];        /* sphere R | core R | cyl R,L | ell a,b,c | par A,B,C |
                               barbell / capped cylinder: R, L, cap radius r >= R |
@@ -1177,6 +1178,35 @@ static double binary_hs_f2(const orc_params* p, const double s[3], double q)
     return (v1 * v1 * s11 + 2.0 * v1 * v2 * s12 + v2 * v2 * s22) / nt;
 }
 
+/* Pringle (Tables I-II, group A): a plate of thickness t = s1 over the disc
+ * x^2 + y^2 <= R^2 (R = s0; x, y along A, B) bent into the saddle
+ * z = alpha x^2 - beta y^2 (alpha, beta = extra[0], extra[1] in 1/A):
+ *   F = drho t sinc(Q_C t / 2) int_disc exp(i (Q_A x + Q_B y + Q_C z(x, y))) dA,
+ * |F|^2 returned (the saddle is not centrosymmetric, F is complex).  The
+ * disc integral in polar coordinates: r by n-point Gauss-Legendre on [0, R],
+ * the angle by the 2n-point midpoint rule on [0, pi) (periodic), pairing
+ * (x, y) with (-x, -y), which share z: 2 cos(Q_A x + Q_B y) exp(i Q_C z). */
+static double pringle_f2(const orc_params* p, const double s[3], double qa, double qb, double qc)
+{
+    int n = p->quad_n, m = 2 * p->quad_n;
+    double R = s[0], t = s[1], al = p->extra[0], be = p->extra[1];
+    const double *gx, *gw;
+    cap_nodes(n, &gx, &gw);
+    double re = 0.0, im = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double r = 0.5 * R * (gx[i] + 1.0), wr = 0.5 * R * gw[i] * r;
+        for (int j = 0; j < m; ++j) {
+            double ph = ORC_PI * (j + 0.5) / m, c = cos(ph), sn = sin(ph);
+            double x = r * c, y = r * sn, z = al * x * x - be * y * y;
+            double w = wr * ORC_PI / m * 2.0 * cos(qa * x + qb * y);
+            re += w * cos(qc * z);
+            im += w * sin(qc * z);
+        }
+    }
+    double pre = (p->sld[0] - p->sld[2]) * t * orc_sinc(0.5 * qc * t);
+    return pre * pre * (re * re + im * im);
+}
+
 /* The squared amplitude of one particle, or for the micelle its scattering
  * per particle (it has incoherent chain terms); for the shape-independent
  * models their cross-section in 1/cm. */
@@ -1185,6 +1215,7 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
     if (shape_independent(p->kind)) return shape_independent_iq(p, s, q);
     if (lamellar(p->kind)) return lamellar_iq(p, s, q);
     if (p->kind == 59) return binary_hs_f2(p, s, q);
+    if (p->kind == 61) return pringle_f2(p, s, qa, qb, qc);
     if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
     if ((p->kind >= 25 && p->kind <= 28) || p->kind == 57 || p->kind == 58) return sphere_family_f2(p, s, q);
     if (p->kind == 45) {
@@ -1240,7 +1271,7 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
 }
 
 /* Orientation matters (the particles from 2 to 12 but the micelle). */
-static int anisotropic(int kind) { return (kind >= 2 && kind != 8 && kind <= 12) || (kind >= 41 && kind <= 48) || kind == 51 || kind == 56; }
+static int anisotropic(int kind) { return (kind >= 2 && kind != 8 && kind <= 12) || (kind >= 41 && kind <= 48) || kind == 51 || kind == 56 || kind == 61; }
 
 /* Sizes scaled by the relative size draw y according to the mask. */
 static void scaled_sizes(const orc_params* p, double y, double s[3])
@@ -1360,6 +1391,8 @@ double orc_mean_volume(const orc_params* p)
         double phi2 = p->extra[0], phi1 = p->phi - phi2;
         return p->phi / (phi1 / vol_sphere(s[0]) + phi2 / vol_sphere(s[1]));
     }
+    case 61: /* pringle: the plate's area times its thickness */
+        return ORC_PI * s[0] * s[0] * s[1] * size_moment(p, (p->poly_mask & 1 ? 2 : 0) + (p->poly_mask & 2 ? 1 : 0));
     case 58: /* pearl necklace: N pearls and N - 1 rods */
         return p->extra[0] * vol_sphere(s[0]) * size_moment(p, (p->poly_mask & 1) ? 3 : 0)
              + (p->extra[0] - 1.0) * ORC_PI * 0.25 * s[2] * s[2] * s[1];

@@ -1834,3 +1834,39 @@ def test_adsorbed_layer_is_the_thin_shell_averaged_over_its_fringes(orc):
         assert avg == pytest.approx(want, rel=2e-2)
         assert orc.form_f2(lay_s, q, (0.0, 0.0, q)) == pytest.approx(
             orc.form_f2(lay, q, (0.0, 0.0, q)) * math.exp(-(q * 15.0) ** 2), rel=1e-13)
+
+
+# ---------------------------------------------------------------- pringle
+
+def _pringle(orc, al, be, qv, n=100, R=60.0, t=10.0):
+    p = W.params(kind="pringle", size=(R, t, 0.0), sld=(1.0, 0.0, 0.0), extra=(al, be, 0, 0), quad_n=n)
+    return orc.form_f2(p, math.sqrt(sum(c * c for c in qv)), qv)
+
+
+@pytest.mark.parametrize("qv", [(0.0, 0.0, 0.0), (0.03, 0.02, 0.01), (0.0, 0.05, 0.04), (0.06, 0.0, 0.0)])
+def test_pringle_flat_is_the_disc(orc, qv):
+    from scipy import special
+    R, t = 60.0, 10.0
+    qab = math.hypot(qv[0], qv[1])
+    x = qab * R
+    lam = 1.0 if x == 0 else 2 * special.j1(x) / x
+    sinc = 1.0 if qv[2] == 0 else math.sin(0.5 * qv[2] * t) / (0.5 * qv[2] * t)
+    f = math.pi * R * R * t * sinc * lam
+    assert _pringle(orc, 0.0, 0.0, qv) == pytest.approx(f * f, rel=1e-9, abs=1e-9 * (math.pi * R * R * t) ** 2)
+
+
+def test_pringle_saddle_against_a_cartesian_quadrature_and_its_symmetry(orc):
+    """The bent plate's disc integral by SciPy's adaptive quadrature in x, y;
+    exchanging the two curvatures is the same body turned by 90 degrees
+    about C and flipped (Q_A <-> Q_B, Q_C -> -Q_C)."""
+    from scipy import integrate
+    R, t, al, be = 60.0, 10.0, 0.004, 0.02
+    qa, qb, qc = 0.03, 0.02, 0.05
+    ph = lambda y, x: qa * x + qb * y + qc * (al * x * x - be * y * y)
+    lim = lambda x: math.sqrt(max(R * R - x * x, 0.0))
+    re, _ = integrate.dblquad(lambda y, x: math.cos(ph(y, x)), -R, R, lambda x: -lim(x), lim, epsabs=0, epsrel=1e-10)
+    im, _ = integrate.dblquad(lambda y, x: math.sin(ph(y, x)), -R, R, lambda x: -lim(x), lim, epsabs=0, epsrel=1e-10)
+    sinc = math.sin(0.5 * qc * t) / (0.5 * qc * t)
+    want = (t * sinc) ** 2 * (re * re + im * im)
+    assert _pringle(orc, al, be, (qa, qb, qc), n=120) == pytest.approx(want, rel=1e-7)
+    assert _pringle(orc, al, be, (qa, qb, qc)) == pytest.approx(_pringle(orc, be, al, (qb, qa, -qc)), rel=1e-12)
