@@ -243,7 +243,7 @@ typedef enum {
                                     (Baxter's factorisation for mixtures);
                                     monodisperse, no separate structure
                                     factor                                    */
-    SANS_ADSORBED_LAYER = 60     /* a layer of excess thickness shell > 0
+    SANS_ADSORBED_LAYER = 60,    /* a layer of excess thickness shell > 0
                                     (adsorbed amount over its bulk density;
                                     SLD sld[0]) on large contrast-matched
                                     particles of radius size[0] at volume
@@ -252,6 +252,14 @@ typedef enum {
                                     (A): phi (3/R) 2 pi (drho shell)^2
                                     exp(-(q extra[0])^2) / q^2; monodisperse,
                                     no structure factor                       */
+    SANS_PRINGLE = 61            /* oriented: a plate of thickness size[1] over
+                                    the disc of radius size[0] in the AB plane,
+                                    bent into the saddle z = extra[0] x^2 -
+                                    extra[1] y^2 (1/A); its disc integral by a
+                                    quad_n-point radial Gauss-Legendre times
+                                    2 quad_n-point angular midpoint rule per
+                                    event; no quadrature mode; poly_mask bits
+                                    0 (radius) and 1 (thickness)              */
 } sans_kind;
 
 /* Structure factor S(q) of the particles (when sq_phi > 0): volume fraction

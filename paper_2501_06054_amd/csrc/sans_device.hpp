@@ -574,7 +574,7 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kMassSurfaceFractal = 49, kGelFit = 50, kSuperball = 51, kLamellarHg = 52,
               kLamellarStackCaille = 53, kLamellarHgStackCaille = 54, kLamellarStackParacrystal = 55,
               kBicelleBeltRough = 56, kRaspberry = 57, kPearlNecklace = 58, kBinaryHardSphere = 59,
-              kAdsorbedLayer = 60 };
+              kAdsorbedLayer = 60, kPringle = 61 };
 
 // Randomly oriented lamellae: the weight per unit volume fraction.
 template <int KIND>
@@ -604,7 +604,7 @@ constexpr bool kSphereFamily = (KIND >= kFuzzySphere && KIND <= kLinearPearls) |
 template <int KIND>
 constexpr bool kAniso = (KIND >= kCylinder && KIND <= kHollowPrismThick && KIND != kMicelle)
                         || (KIND >= kEllipticalCylinder && KIND <= kFccParacrystal) || KIND == kSuperball
-                        || KIND == kBicelleBeltRough;
+                        || KIND == kBicelleBeltRough || KIND == kPringle;
 
 // Bodies of revolution about C: cylinders (plain, hollow, core-shell),
 // barbell, capped cylinder (only the axis projection Q.C and Q_AB enter, the
@@ -671,6 +671,36 @@ __device__ __forceinline__ float superball_sum(const TraceArgs& a, float ta, flo
         sum = __builtin_fmaf(cx, inner, sum);
     }
     return sum;
+}
+
+// The pringle's |F|^2: the saddle-bent plate's disc integral over the host's
+// polar rule (cap_nodes: 2 n^2 nodes of x, then y, then z = alpha x^2 - beta
+// y^2, then the weights with the (x, y) <-> (-x, -y) pairing folded in),
+// exp(i (Q_A x + Q_B y + Q_C z)) summed into its real and imaginary parts;
+// the thickness factor t sinc(Q_C t / 2).  y_s scales the plate's radius and
+// y_t its thickness.
+__device__ __forceinline__ float pringle_f2(const TraceArgs& a, double ys, double yt, double qa, double qb,
+                                            double qc)
+{
+    const int m = 2 * a.cap_n * a.cap_n;
+    const float* __restrict__ xs = a.cap_nodes;
+    const float* __restrict__ yv = xs + m;
+    const float* __restrict__ zs = yv + m;
+    const float* __restrict__ ws = zs + m;
+    const float ta = (float)(qa * ys), tb = (float)(qb * ys), tc = (float)(qc * ys * ys);
+    float re = 0.0f, im = 0.0f;
+#pragma unroll 4
+    for (int k = 0; k < m; ++k) {
+        float s1, c1, s2, c2;
+        sincos_f(__builtin_fmaf(ta, xs[k], tb * yv[k]), s1, c1);
+        sincos_f(tc * zs[k], s2, c2);
+        const float w = ws[k] * c1;
+        re = __builtin_fmaf(w, c2, re);
+        im = __builtin_fmaf(w, s2, im);
+    }
+    const double t = a.size[1] * yt;
+    const float pre = a.contrast * (float)t * sinc_d(0.5 * qc * t) * (float)(ys * ys);
+    return pre * pre * __builtin_fmaf(re, re, im * im);
 }
 
 // sin(x)/x and cos x together (thin-walled prism): both from one reduction;
@@ -1266,6 +1296,8 @@ __device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, doub
     } else if constexpr (KIND == kScParacrystal || KIND == kBccParacrystal || KIND == kFccParacrystal) {
         const float r = (float)s[0];
         return a.contrast * k43pi * r * r * r * sph3j_d(q * s[0]);
+    } else if constexpr (KIND == kPringle) {
+        return 0.0f;   // |F|^2 comes from pringle_f2 (F is complex)
     } else if constexpr (KIND == kSuperball) {
         const float r = (float)s[0];
         return a.contrast * r * r * r * superball_sum(a, (float)(qa * s[0]), (float)(qb * s[0]), (float)(qc * s[0]));
@@ -1392,6 +1424,8 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
         return (float)kPi * __builtin_fmaf(a.cs_core, core, a.cs_shell * outer);
     } else if constexpr (KIND == kScParacrystal || KIND == kBccParacrystal || KIND == kFccParacrystal) {
         return a.contrast * k43pi * s[0] * s[0] * s[0] * sph3j_f(q * s[0]);
+    } else if constexpr (KIND == kPringle) {
+        return 0.0f;   // no quadrature mode for the pringle (refused at validation)
     } else if constexpr (KIND == kSuperball) {
         return a.contrast * s[0] * s[0] * s[0] * superball_sum(a, qa * s[0], qb * s[0], qc * s[0]);
     } else if constexpr (KIND == kCoreShellParallelepiped) {
@@ -1713,6 +1747,8 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
             f2 = shape_iq<KIND>(a, a.size[0], qd);
         } else if constexpr (kLamellar<KIND>) {
             f2 = lamellar_f2<KIND>(a, qd);
+        } else if constexpr (KIND == kPringle) {
+            f2 = pringle_f2(a, (a.poly_mask & 1) ? y : 1.0, (a.poly_mask & 2) ? y : 1.0, qa, qb, qc);
         } else if constexpr (kSphereFamily<KIND>) {
             f2 = sphere_family_f2<KIND>(a, (a.poly_mask & 1) ? a.size[0] * y : a.size[0], qd);
         } else {

@@ -554,7 +554,8 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 57: batch_tile<57>(a, tl.first, tl.count, hist, tab); break;
         case 58: batch_tile<58>(a, tl.first, tl.count, hist, tab); break;
         case 59: batch_tile<59>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<60>(a, tl.first, tl.count, hist, tab); break;
+        case 60: batch_tile<60>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<61>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;
@@ -848,6 +849,7 @@ TraceFn pick_trace(int kind, int mode, int tally)
         SANS_CASE(58)
         SANS_CASE(59)
         SANS_CASE(60)
+        SANS_CASE(61)
     }
 #undef SANS_CASE
     return nullptr;
@@ -923,6 +925,7 @@ HistFn pick_hist(int kind, int mode)
         SANS_CASE(58)
         SANS_CASE(59)
         SANS_CASE(60)
+        SANS_CASE(61)
     }
 #undef SANS_CASE
     return nullptr;
@@ -995,6 +998,7 @@ EmitFn pick_emit(int kind, int mode)
         SANS_CASE(58)
         SANS_CASE(59)
         SANS_CASE(60)
+        SANS_CASE(61)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1067,6 +1071,7 @@ DebugFn pick_debug(int kind, int mode)
         SANS_CASE(58)
         SANS_CASE(59)
         SANS_CASE(60)
+        SANS_CASE(61)
     }
 #undef SANS_CASE
     return nullptr;
@@ -1136,6 +1141,7 @@ PqFn pick_pq(int kind)
     case 58: return k_pq_avg<58>;
     case 59: return k_pq_avg<59>;
     case 60: return k_pq_avg<60>;
+    case 61: return k_pq_avg<61>;
     }
     return nullptr;
 }
@@ -1201,7 +1207,7 @@ bool is_aniso(int kind)
 {
     return (kind >= SANS_CYLINDER && kind <= SANS_HOLLOW_PRISM_THICK && kind != SANS_POLYMER_MICELLE)
            || (kind >= SANS_ELLIPTICAL_CYLINDER && kind <= SANS_FCC_PARACRYSTAL) || kind == SANS_SUPERBALL
-           || kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH;
+           || kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH || kind == SANS_PRINGLE;
 }
 
 // Floats of the per-model node rule in device memory: the end caps' rule
@@ -1213,6 +1219,7 @@ size_t rule_floats(const sans_params& p)
     if (p.kind == SANS_LAMELLAR_STACK_CAILLE || p.kind == SANS_LAMELLAR_HG_STACK_CAILLE) return (size_t)p.extra[0];
     if (p.kind == SANS_PEARL_NECKLACE) return 2 * (size_t)p.quad_n;
     if (p.kind == SANS_BINARY_HARD_SPHERE) return 4 * 32;
+    if (p.kind == SANS_PRINGLE) return 8 * (size_t)p.quad_n * p.quad_n;
     return 0;
 }
 
@@ -1232,6 +1239,25 @@ void fill_nodes(const sans_params& p, float* out, const float* base, TraceArgs& 
         const double euler_gamma = 0.57721566490153286061;
         out[0] = 0.0f;
         for (size_t k = 1; k < nr; ++k) out[k] = (float)(euler_gamma + std::log(kPi * (double)k));
+    } else if (p.kind == SANS_PRINGLE) {
+        // polar rule on the disc: r by n-point Gauss-Legendre on [0, R], the
+        // angle by the 2n-point midpoint rule on [0, pi); (x, y) pairs with
+        // (-x, -y) (same z), so the weight carries 2 cos(Q_A x + Q_B y)'s 2
+        const int n = p.quad_n, m = 2 * n, tot = n * m;
+        std::vector<double> gx(n), gw(n);
+        host::gauss_legendre(n, gx.data(), gw.data());
+        const double R = p.size[0], al = p.extra[0], be = p.extra[1];
+        for (int i = 0; i < n; ++i) {
+            const double r = 0.5 * R * (gx[i] + 1.0), wr = 0.5 * R * gw[i] * r;
+            for (int j = 0; j < m; ++j) {
+                const double ph = kPi * (j + 0.5) / m, x = r * std::cos(ph), y = r * std::sin(ph);
+                const int k = i * m + j;
+                out[k] = (float)x;
+                out[tot + k] = (float)y;
+                out[2 * tot + k] = (float)(al * x * x - be * y * y);
+                out[3 * tot + k] = (float)(2.0 * wr * kPi / m);
+            }
+        }
     } else if (p.kind == SANS_BINARY_HARD_SPHERE) {
         // Baxter's factor functions for the mixture, Q_ij(r) = a_i/2 (r^2 - d_ij^2)
         // + b_i (r - d_ij) on (d_i - d_j)/2 < r < d_ij: 16 Gauss-Legendre nodes
@@ -1298,7 +1324,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 60) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 61) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -1318,7 +1344,7 @@ int validate(const sans_params* p)
                            || p->kind == SANS_BCC_PARACRYSTAL || p->kind == SANS_FCC_PARACRYSTAL
                            || p->kind == SANS_LAMELLAR_HG || p->kind == SANS_LAMELLAR_STACK_CAILLE
                            || p->kind == SANS_LAMELLAR_STACK_PARACRYSTAL
-                           || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH;
+                           || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH || p->kind == SANS_PRINGLE;
     int nsize = (p->kind <= 1 || p->kind == SANS_SUPERBALL || p->kind == SANS_ADSORBED_LAYER) ? 1 : (two_sizes ? 2 : 3);
     if (is_shape_independent(p->kind))
         nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK
@@ -1340,6 +1366,15 @@ int validate(const sans_params* p)
         if (p->poly > 0.0 && p->poly_mask != 7)
             return fail(SANS_E_UNSUPPORTED, "barbell / capped cylinder: poly_mask must be 7 (all sizes)");
         if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
+    }
+    if (p->kind == SANS_PRINGLE) {
+        if (!(finite(p->extra[0]) && finite(p->extra[1])))
+            return fail(SANS_E_INVALID_ARG, "pringle: curvatures extra[0], extra[1] must be finite");
+        if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
+        if (p->mode == SANS_MODE_QUAD)
+            return fail(SANS_E_UNSUPPORTED, "pringle: no quadrature mode (2 quad_n^2 nodes per orientation node)");
+        if (p->poly > 0.0 && (p->poly_mask & 4))
+            return fail(SANS_E_UNSUPPORTED, "pringle: poly_mask bits 0 (radius) and 1 (thickness) only");
     }
     if (p->kind == SANS_ADSORBED_LAYER) {
         if (!(p->shell > 0.0 && finite(p->shell) && p->extra[0] >= 0.0 && finite(p->extra[0])))
@@ -1831,6 +1866,7 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
         a.mic_d = p->extra[3];
     }
     if (p->kind == SANS_SUPERBALL) a.cap_n = p->quad_n;
+    if (p->kind == SANS_PRINGLE) a.cap_n = p->quad_n;
     if (p->kind == SANS_ADSORBED_LAYER) {
         a.lam_c = (float)(6.0 * kPi / p->size[0]);
         a.sd_sig = p->extra[0];

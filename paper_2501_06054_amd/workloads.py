@@ -33,7 +33,7 @@ EXTRA_KINDS = ("barbell", "capped_cylinder", "hollow_prism", "micelle", "hollow_
                "elliptical_cylinder", "core_shell_bicelle", "core_shell_parallelepiped",
                "core_shell_bicelle_elliptical", "stacked_disks", "sc_paracrystal", "bcc_paracrystal",
                "fcc_paracrystal", "superball", "core_shell_bicelle_elliptical_belt_rough", "raspberry",
-               "pearl_necklace", "binary_hard_sphere")
+               "pearl_necklace", "binary_hard_sphere", "pringle")
 #: randomly oriented lamellae (weight per unit volume fraction phi)
 LAMELLAR_KINDS = ("lamellar_hg", "lamellar_stack_caille", "lamellar_hg_stack_caille", "lamellar_stack_paracrystal",
                   "adsorbed_layer")

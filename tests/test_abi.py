@@ -194,6 +194,9 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
           sq_radius=50.0), "SANS_E_UNSUPPORTED"),
     (dict(kind="adsorbed_layer", size=(1000.0, 0.0, 0.0), shell=0.0), "SANS_E_INVALID_ARG"),
     (dict(kind="adsorbed_layer", size=(1000.0, 0.0, 0.0), shell=2.0, poly=0.1), "SANS_E_UNSUPPORTED"),
+    (dict(kind="pringle", size=(60.0, 10.0, 0.0), extra=(0.001, 0.02, 0, 0), mode="quad", orient_kind="isotropic"),
+     "SANS_E_UNSUPPORTED"),
+    (dict(kind="pringle", size=(60.0, 0.0, 0.0), extra=(0.001, 0.02, 0, 0)), "SANS_E_INVALID_ARG"),
 ])
 def test_capped_body_params_rejected_without_gpu(S, over, code):
     from paper_2501_06054_amd import workloads as W
@@ -205,7 +208,7 @@ def test_capped_body_params_rejected_without_gpu(S, over, code):
 def test_unknown_kind_rejected_without_gpu(S):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=1.0))
-    sp.kind = 61
+    sp.kind = 62
     h = C.c_void_p()
     assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED
 

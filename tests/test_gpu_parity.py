@@ -69,7 +69,7 @@ def check_detector(d_gpu, d_orc, where="", count=None, w_max=None):
 
 
 # models judged pixel by pixel with the summed per-neutron bar
-SUMMED_BAR = ("barbell", "capped_cylinder", "hollow_prism", "superball")
+SUMMED_BAR = ("barbell", "capped_cylinder", "hollow_prism", "superball", "pringle")
 
 
 def oracle_detector(p, n, seed, first=0):
@@ -343,6 +343,12 @@ PER_NEUTRON = {
                                                  sld=(3e-6, 0.5e-6, 6.3e-6), phi=0.25, extra=(0.01, 0, 0, 0)), 30011),
     "adsorbed_layer": (W.params(kind="adsorbed_layer", size=(2000.0, 0, 0), shell=2.5, sld=(1.5e-6, 0, 6.3e-6),
                                 extra=(12.0, 0, 0, 0), phi=0.05), 30011),
+    # pringle (complex amplitude, a polar rule per event)
+    "pringle_iso": (W.params(kind="pringle", size=(60.0, 10.0, 0), extra=(0.001, 0.02, 0, 0), quad_n=16,
+                             orient_kind="isotropic"), 10011),
+    "pringle_gauss_poly": (W.params(kind="pringle", size=(45.0, 8.0, 0), extra=(0.01, 0.004, 0, 0), quad_n=12,
+                                    orient_kind="gaussian", orient_mean=(0.7, 0.3, 1.1),
+                                    orient_sigma=(0.2, 0.2, 0.2), poly=0.1, poly_mask=3), 10011),
 }
 
 
@@ -375,7 +381,7 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "mass_surface_fractal", "gel_fit", "sticky_coreshell", "square_well_poly_sphere",
              "oriented_superball", "lamellar_caille", "lamellar_hg", "lamellar_stack_paracrystal",
              "belt_bicelle_gauss", "raspberry_poly", "pearl_necklace", "binary_hard_sphere",
-             "adsorbed_layer"]
+             "adsorbed_layer", "pringle_iso"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
