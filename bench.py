@@ -93,6 +93,12 @@ STEP = {
     "caille_term":   ((18,  3,  0,  6, 1, 0), 24),  # one sheet pair of a Caille stack: FP64 phase reduction, cos, exp
     "neck_node":     ((34,  6,  0,  6, 2, 0), 44),  # necklace rod rule node: two sinc (one FP64 phase), two fma
     "neck_unit":     ((8,   0,  0,  0, 0, 0), 12),  # necklace pair-sum step: power, three fma
+    "bhs_node":      ((16,  3,  0,  0, 0, 0), 20),  # binary spheres, one node of a Qhat_ij integral: sincos, two fma
+    "bhs_mat":       ((24,  0,  0,  0, 1, 0), 40),  # binary spheres: Qhat^H Qhat, its inverse, v^T S v
+    "rasp_F":        ((36,  0,  0, 12, 0, 0), 60),  # raspberry: two sphere amplitudes, sinc(qD), the pair sum
+    "belt_F":        ((56,  0,  0, 34, 1, 2), 80),  # belt bicelle: two 2 J1(x)/x, two sinc, roughness exp
+    "ads_I":         ((6,   0,  0,  2, 1, 1), 8),   # adsorbed layer: (drho t)^2 exp(-(q sigma)^2) / q^2
+    "pr_node":       ((30,  6,  0,  0, 0, 0), 40),  # pringle, one polar node: two sincos, three fma
     "weight":        ((3,   0,  0,  2, 0, 0), 3),   # A11
     "detector":      ((0,   5,  0, 23, 0, 1), 0),   # A12: plane crossing (quotient), pixel
     "tally":         ((0,   2,  0,  0, 0, 0), 0),   # A13: address; the add itself is a memory op
@@ -146,6 +152,14 @@ PATHS = {
     # pearl necklace: pearl amplitude, 24 rule nodes, 9 pair-sum steps
     "pearl_necklace": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["sphere_F"] + ["neck_node"] * 24
                       + ["neck_unit"] * 9,
+    "binary_hard_sphere": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["sphere_F"] * 2 + ["bhs_node"] * 64
+                          + ["bhs_mat"],
+    "raspberry": COMMON + ["philox_block"] * 3 + ["uniform"] * 9 + ["size_draw", "rasp_F"],
+    "oriented_belt_bicelle": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
+                             + ["qvec"] + ["orient_angle"] * 3 + ["project_abc", "belt_F"],
+    "adsorbed_layer": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["ads_I"],
+    "oriented_pringle": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
+                        + ["qvec", "iso_orient", "project_abc"] + ["pr_node"] * 512,
 }
 # Exact-average paths, per quadrature node (76 x 76 = 5776 nodes per neutron),
 # all FP32:

@@ -354,6 +354,54 @@ def pearl_necklace() -> dict:
                               extra=(10.0, 0.0, 0.0, 0.0), quad_n=24, phi=0.02, nx=256, ny=256))
 
 
+def binary_hard_sphere() -> dict:
+    """Binary hard-sphere mixture: spheres of 50 A (SLD 1e-6) at volume
+    fraction 0.2 and of 20 A (4e-6) at 0.1 in 6.3e-6 solvent, with their
+    Percus-Yevick partial structure factors, 256x256, 1e9 neutrons."""
+    return dict(name="binary_hard_sphere", n=10**9, seed=29, exp_id=0,
+                params=params(kind="binary_hard_sphere", size=(50.0, 20.0, 0.0), sld=(1e-6, 4e-6, 6.3e-6),
+                              phi=0.3, extra=(0.1, 0.0, 0.0, 0.0), nx=256, ny=256))
+
+
+def raspberry() -> dict:
+    """Raspberries: 80 A spheres (SLD 1e-6, Schulz 0.1) carrying 40 spheres of
+    15 A (4e-6) sunk 0.3 of their diameter, solvent 6.3e-6, volume fraction
+    0.05, 256x256, 1e9 neutrons."""
+    return dict(name="raspberry", n=10**9, seed=30, exp_id=0,
+                params=params(kind="raspberry", size=(80.0, 15.0, 0.0), sld=(1e-6, 4e-6, 6.3e-6),
+                              extra=(40.0, 0.3, 0.0, 0.0), poly=0.1, poly_mask=1, phi=0.05, nx=256, ny=256))
+
+
+def oriented_belt_bicelle() -> dict:
+    """Elliptical bicelles with a belt and rough interfaces (core 25 x 42.5 A,
+    length 40 A; faces 5 A; belt 6 A; roughness 3 A), Gaussian spread 10 deg
+    on three angles, 256x256, 1e9 neutrons."""
+    return dict(name="oriented_belt_bicelle", n=10**9, seed=31, exp_id=0,
+                params=params(kind="core_shell_bicelle_elliptical_belt_rough", size=(25.0, 40.0, 0.0), shell=6.0,
+                              sld=(1e-6, 4e-6, 6.3e-6), extra=(5.0, 2.5e-6, 1.7, 3.0), phi=0.01,
+                              orient_kind="gaussian", orient_mean=(60 * DEG, 20 * DEG, 30 * DEG),
+                              orient_sigma=(10 * DEG, 10 * DEG, 10 * DEG), nx=256, ny=256))
+
+
+def adsorbed_layer() -> dict:
+    """A 2.5 A (excess) polymer layer (SLD 1.5e-6) on contrast-matched 2000 A
+    particles at volume fraction 0.05, smeared by 12 A, 256x256, 1e9
+    neutrons."""
+    return dict(name="adsorbed_layer", n=10**9, seed=32, exp_id=0,
+                params=params(kind="adsorbed_layer", size=(2000.0, 0.0, 0.0), shell=2.5, sld=(1.5e-6, 0.0, 6.3e-6),
+                              extra=(12.0, 0.0, 0.0, 0.0), phi=0.05, nx=256, ny=256))
+
+
+def oriented_pringle() -> dict:
+    """Pringles: 60 A plates 10 A thick bent into the saddle 0.001 x^2 - 0.02
+    y^2, isotropic orientation, a 16 x 32 polar rule per event, 256x256, 1e8
+    neutrons."""
+    return dict(name="oriented_pringle", n=10**8, seed=33, exp_id=0,
+                params=params(kind="pringle", size=(60.0, 10.0, 0.0), sld=(1e-6, 0, 6.3e-6),
+                              extra=(0.001, 0.02, 0.0, 0.0), quad_n=16, phi=0.01, orient_kind="isotropic",
+                              nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -382,6 +430,11 @@ WORKLOADS = {
     "oriented_superball": oriented_superball,
     "lamellar_caille": lamellar_caille,
     "pearl_necklace": pearl_necklace,
+    "binary_hard_sphere": binary_hard_sphere,
+    "raspberry": raspberry,
+    "oriented_belt_bicelle": oriented_belt_bicelle,
+    "adsorbed_layer": adsorbed_layer,
+    "oriented_pringle": oriented_pringle,
 }
 
 
