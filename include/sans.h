@@ -18,9 +18,10 @@
  *     distributions");
  *   - neutrons are independent and the detector is summed with atomic
  *     updates (Methods, "Acceleration schemes").
- * Instrument, weight, random numbers (Philox4x32-10), tables and the
- * hard-sphere Percus-Yevick S(Q) are the library's own readings where the
- * paper is silent; they are documented field by field below.
+ * Instrument, weight, random numbers (Philox4x32-10), tables, the model
+ * formulas (the paper names its models but gives few formulas) and the
+ * structure factors are the library's own readings where the paper is
+ * silent; they are documented field by field below.
  *
  * Conventions for every entry point
  *   - Return value: SANS_OK (0) or a negative SANS_E_* status; the text of
@@ -60,7 +61,9 @@ extern "C" {
 #define SANS_E_HIP (-4)         /* a HIP runtime call failed (see last error)  */
 #define SANS_E_DOMAIN (-5)      /* inputs outside a model's valid domain        */
 
-/* Particle models (Tables I and II of the paper; this library provides five). */
+/* Scattering models (Tables I and II of the paper): particles, lamellae and
+ * shape-independent cross-sections, 62 kinds; the structure factors are
+ * selected separately (sans_sq_kind). */
 typedef enum {
     SANS_SPHERE = 0,           /* size[0] = R                                   */
     SANS_CORE_SHELL_SPHERE = 1,/* size[0] = core R, shell = thickness            */
