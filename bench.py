@@ -82,8 +82,8 @@ STEP = {
     "shell_F":       ((32,  0,  0,  8, 0, 0), 44),  # one vesicle shell: two 3 j1(x)/x (FP64 phases), volumes
     "ellcyl_F":      ((24,  0,  0, 15, 0, 1), 39),  # elliptical cylinder: |(a Q_A, b Q_B)| (sqrt), sinc, 2 J1(x)/x
     "paracrystal_Z": ((54,  6,  0, 60, 1, 3), 60),  # 3 x (Q.v_k, FP64 half-phase reduction, sin^2, quotient), e
-    "pev_I":         ((2,   0,  0, 500, 0, 3), 0),  # excluded-volume chain: two FP64 incomplete gammas (~30 series
-                                                    # or continued-fraction steps of 4 ops each, exp, log)
+    "pev_I":         ((196, 0,  0,  4, 64, 0), 256),  # excluded-volume chain: two 32-node rules of t^(s-1) exp(-U t)
+                                                      # (a multiply, an exp and an fma per node)
     "py_sq":         ((15,  0,  0,  0, 1, 0), 25),  # A10: series in x^2, 1/(1 + 24 phi G/x)
     "sticky_sq":     ((27,  0,  0,  0, 1, 0), 50),  # adhesive spheres: two series in k^2, A^2 + B^2, reciprocal
     "msf_I":         ((8,   0,  0,  3, 3, 0), 10),  # mass-surface fractal: two log2, one exp2

@@ -786,6 +786,10 @@ __device__ __forceinline__ float micelle_f2(const TraceArgs& a, double R, double
     return __builtin_fmaf(amp, amp, a.mic_n * a.mic_bc * a.mic_bc * __builtin_fmaf(-ps, ps, pc));
 }
 
+// The excluded-volume chain's rule: nodes per integral and the largest U it serves.
+constexpr int kPevRuleNodes = 32;
+constexpr double kPevRuleMaxU = 40.0;
+
 // Lower incomplete gamma g(s, x) = Gamma(s) P(s, x), FP64: its power series
 // below x = s + 1, else Gamma(s) less Legendre's continued fraction for the
 // upper one (modified Lentz); gs = Gamma(s).
@@ -924,11 +928,25 @@ __device__ __forceinline__ float shape_iq(const TraceArgs& a, double len, double
         return __builtin_fmaf(a.si_scale, net, (float)a.si_c * __expf(-(float)(q * q * a.si_d)));
     } else {
         // polymer with excluded volume: (g(s1, U)/U^s1 - g(s2, U)/U^s2)/nu with
-        // the lower incomplete gamma g, s1 = 1/(2 nu), s2 = 1/nu (FP64); a series
-        // below U = 1e-3
+        // the lower incomplete gamma g, s1 = 1/(2 nu), s2 = 1/nu, i.e.
+        // int_0^1 t^(s-1) exp(-U t) dt for each s: a series below U = 1e-3; up to
+        // U = 40 the host's rule (t = w^6 makes the integrands smooth in w;
+        // 32 Gauss-Legendre nodes, relative error below 1e-9 there) in FP32;
+        // beyond, FP64 incomplete gammas
         const double qr = q * len;
         const double u = qr * qr * a.si_a, s1 = a.si_c, s2 = a.si_d;
         double v;
+        if (u >= 1e-3 && u <= kPevRuleMaxU) {
+            const float uf = (float)u;
+            const float* __restrict__ nd = a.cap_nodes;
+            float x1 = 0.0f, x2 = 0.0f;
+#pragma unroll 8
+            for (int k = 0; k < kPevRuleNodes; ++k) {
+                x1 = __builtin_fmaf(nd[kPevRuleNodes + k], __expf(-uf * nd[k]), x1);
+                x2 = __builtin_fmaf(nd[3 * kPevRuleNodes + k], __expf(-uf * nd[2 * kPevRuleNodes + k]), x2);
+            }
+            return a.si_scale * (x1 - x2) * (float)(1.0 / a.si_b);
+        }
         if (u < 1e-3) {
             double x1 = 0.0, x2 = 0.0, t = 1.0;
             for (int k = 0; k < 4; ++k) {

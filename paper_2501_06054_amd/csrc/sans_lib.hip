@@ -1220,6 +1220,7 @@ size_t rule_floats(const sans_params& p)
     if (p.kind == SANS_PEARL_NECKLACE) return 2 * (size_t)p.quad_n;
     if (p.kind == SANS_BINARY_HARD_SPHERE) return 4 * 32;
     if (p.kind == SANS_PRINGLE) return 8 * (size_t)p.quad_n * p.quad_n;
+    if (p.kind == SANS_POLYMER_EXCL_VOLUME) return 4 * (size_t)kPevRuleNodes;
     return 0;
 }
 
@@ -1239,6 +1240,19 @@ void fill_nodes(const sans_params& p, float* out, const float* base, TraceArgs& 
         const double euler_gamma = 0.57721566490153286061;
         out[0] = 0.0f;
         for (size_t k = 1; k < nr; ++k) out[k] = (float)(euler_gamma + std::log(kPi * (double)k));
+    } else if (p.kind == SANS_POLYMER_EXCL_VOLUME) {
+        // int_0^1 t^(s-1) exp(-U t) dt with t = w^6: 6 w^(6 s - 1) exp(-U w^6) dw,
+        // smooth in w, by 32-point Gauss-Legendre on [0, 1]; s = 1/(2 nu), 1/nu
+        const int n = kPevRuleNodes;
+        double gx[kPevRuleNodes], gw[kPevRuleNodes];
+        host::gauss_legendre(n, gx, gw);
+        const double nu = p.extra[1], sv[2] = {0.5 / nu, 1.0 / nu};
+        for (int h = 0; h < 2; ++h)
+            for (int k = 0; k < n; ++k) {
+                const double w = 0.5 * (gx[k] + 1.0);
+                out[2 * h * n + k] = (float)std::pow(w, 6.0);
+                out[(2 * h + 1) * n + k] = (float)(6.0 * 0.5 * gw[k] * std::pow(w, 6.0 * sv[h] - 1.0));
+            }
     } else if (p.kind == SANS_PRINGLE) {
         // polar rule on the disc: r by n-point Gauss-Legendre on [0, R], the
         // angle by the 2n-point midpoint rule on [0, pi); (x, y) pairs with
