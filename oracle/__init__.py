@@ -56,7 +56,7 @@ class OrcParams(C.Structure):
         ("nx", C.c_int32), ("ny", C.c_int32),
         ("table_size", C.c_int32), ("quad_n", C.c_int32),
         ("poly_kind", C.c_int32), ("sq_kind", C.c_int32),
-        ("extra", C.c_double * 4), ("sq_extra", C.c_double * 2),
+        ("extra", C.c_double * 4), ("sq_extra", C.c_double * 2), ("mu_att", C.c_double),
     ]
 
 
@@ -162,6 +162,7 @@ def to_params(p: dict) -> OrcParams:
     for k, v in enumerate(p.get("extra", (0.0, 0.0, 0.0, 0.0))):
         o.extra[k] = float(v)
     o.sq_kind = SQ_KIND[p.get("sq_kind", "hard_sphere")]
+    o.mu_att = float(p.get("mu_att", 0.0))
     for k, v in enumerate(p.get("sq_extra", (0.0, 0.0))):
         o.sq_extra[k] = float(v)
     return o

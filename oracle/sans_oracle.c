@@ -120,6 +120,8 @@ typedef struct {
                               core-shell cylinder: extra[0] = end-face shell */
     double sq_extra[2];    /* adhesive spheres: stickiness tau; square well:
                               depth (kT) and width (in diameters)           */
+    double mu_att;         /* attenuation coefficient of the sample (1/m);
+                              0 -> none                                     */
 } orc_params;
 
 /* Surrogate mode (mode 2): a network replaces the exact average; set with
@@ -1811,6 +1813,18 @@ static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_
     }
     double sq = struct_factor(p, q);
     double w = len * 1e10 * cx->prefactor * f2 * sq;
+    /* attenuation: exp(-mu (path before the scattering point + path after it
+       along kf to where the slab is left)) */
+    if (p->mu_att > 0.0) {
+        double tout = INFINITY;
+        for (int a = 0; a < 3; ++a) {
+            double tt = INFINITY;
+            if (kf[a] > 0.0) tt = (half[a] - rs[a]) / kf[a];
+            if (kf[a] < 0.0) tt = (-half[a] - rs[a]) / kf[a];
+            if (tt < tout) tout = tt;
+        }
+        w *= exp(-p->mu_att * ((s - s_in) + tout));
+    }
     for (int a = 0; a < 3; ++a) {
         ev.qv[a] = qv[a];
         ev.ang[a] = ang[a];

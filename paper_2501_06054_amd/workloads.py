@@ -73,6 +73,7 @@ SAMPLE_DEFAULTS = dict(
     orient_kind="fixed", orient_mean=(0.0, 0.0, 0.0), orient_sigma=(0.0, 0.0, 0.0),
     table_size=4096, quad_n=76,
     extra=(0.0, 0.0, 0.0, 0.0),
+    mu_att=0.0,
 )
 
 

@@ -1870,3 +1870,39 @@ def test_pringle_saddle_against_a_cartesian_quadrature_and_its_symmetry(orc):
     want = (t * sinc) ** 2 * (re * re + im * im)
     assert _pringle(orc, al, be, (qa, qb, qc), n=120) == pytest.approx(want, rel=1e-7)
     assert _pringle(orc, al, be, (qa, qb, qc)) == pytest.approx(_pringle(orc, be, al, (qb, qa, -qc)), rel=1e-12)
+
+
+# ---------------------------------------------------------------- attenuation
+
+def test_attenuation_in_the_forward_limit(orc):
+    """Scattering by a vanishing angle keeps the whole path a chord through
+    the slab, before and after the scattering point together: every weight
+    is damped by exp(-mu d / k_z) ~ exp(-mu d), whatever the depth of the
+    event (a missing or doubled part of the path would make it depend on
+    the depth); mu = 0 changes nothing."""
+    base = W.params(kind="sphere", size=(50.0, 0, 0), cone_alpha=1e-6, sample_d=0.001)
+    att = dict(base, mu_att=200.0)
+    _, w0, _ = orc.trace_debug(base, 2000, 11)
+    _, w1, _ = orc.trace_debug(att, 2000, 11)
+    hit = w0 > 0
+    assert hit.sum() > 1900
+    ratio = w1[hit] / w0[hit]
+    assert np.allclose(ratio, math.exp(-200.0 * 0.001), rtol=2e-6, atol=0)
+    _, wz, _ = orc.trace_debug(dict(base, mu_att=0.0), 2000, 11)
+    assert np.array_equal(wz, w0)
+
+
+def test_attenuation_bounds_at_wide_angles(orc):
+    """At wide angles the path is at least the part before the event and at
+    most that plus the slab's diagonal: weights fall by factors between
+    exp(-mu (chord + diagonal)) and 1, and smaller ones for larger mu."""
+    base = W.params(kind="sphere", size=(50.0, 0, 0), cone_alpha=1.2, sample_d=0.002)
+    _, w0, _ = orc.trace_debug(base, 3000, 12)
+    _, w1, _ = orc.trace_debug(dict(base, mu_att=100.0), 3000, 12)
+    _, w2, _ = orc.trace_debug(dict(base, mu_att=300.0), 3000, 12)
+    hit = w0 > 0
+    diag = math.sqrt(0.010 ** 2 + 0.010 ** 2 + 0.002 ** 2)
+    r1, r2 = w1[hit] / w0[hit], w2[hit] / w0[hit]
+    assert np.all(r1 <= 1.0) and np.all(r1 >= math.exp(-100.0 * (0.0021 + diag)))
+    assert np.all(r2 < r1)
+    assert np.allclose(r2, r1 ** 3, rtol=1e-10, atol=0)   # the same path: exp(-3 x) = exp(-x)^3
