@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SANS_ABI_VERSION 4u
+#define SANS_ABI_VERSION 5u
 
 /* Status codes. */
 #define SANS_OK 0
@@ -385,6 +385,15 @@ typedef struct {
     double extra[4];         /* model parameters beyond size and shell (see
                                 sans_kind; unused entries 0)                   */
     double sq_extra[2];      /* structure-factor parameters (sans_sq_kind)     */
+    double mu_att;           /* attenuation coefficient of the sample (1/m,
+                                >= 0): the weight is damped by exp(-mu_att
+                                (path inside the slab before the scattering
+                                point + path after it to where the scattered
+                                neutron leaves the slab)); 0 = none.
+                                Attenuated runs tally with atomics (GLOBAL,
+                                or XCD when asked for), whatever `tally`
+                                asks; the batched launch and the surrogate
+                                mode refuse them (SANS_E_UNSUPPORTED)       */
 } sans_params;
 
 typedef struct sans_model_s* sans_model_t;

@@ -75,6 +75,8 @@ struct TraceArgs {
     double half_x, half_y, half_z;
     double clear_x, clear_y;      // the half-widths less 1e-9 of themselves
     double omc;                   // 1 - cos(alpha)
+    double mu_att;                // attenuation coefficient (1/m)
+    int32_t att_on;               // mu_att > 0 (an integer: the branch stays scalar)
     double det_z, det_hw, det_hh;
     double inv_px, inv_py;        // nx / det_w, ny / det_h
     double wscale;                // 1e10 * dOmega * phi / <V>  (per metre of path)
@@ -1629,7 +1631,10 @@ struct Event {
 // Traces neutron i.  tab_size/tab_norm point to the LDS copies of the
 // tables; lq to the LDS copy of the quadrature nodes (QUAD mode; with
 // nparts > 1 the weight is this part's share of the exact average).
-template <int KIND, int MODE>
+// ATT: the sample's attenuation is compiled in (the atomic-tally and
+// per-neutron kernels; the others leave it out and the host routes attenuated
+// runs to the atomic tallies)
+template <int KIND, int MODE, bool ATT = false>
 __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
                                                const double* tab_size, const double* tab_norm,
                                                const float* lq, int part = 0, int nparts = 1)
@@ -1718,6 +1723,18 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     const bool on_det = in_sample && forward && fxp >= 0.0 && fxp < (double)a.nx && fyp >= 0.0
                         && fyp < (double)a.ny;
 
+    // attenuation along the path inside the slab, before the scattering point
+    // and after it along k_f to the face where it leaves (when asked for)
+    float att = 1.0f;
+    if (ATT && a.att_on) {
+        const double o[3] = {rx, ry, rz}, dv[3] = {fx, fy, fz}, hw[3] = {a.half_x, a.half_y, a.half_z};
+        double tout = 1e300;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (dv[c] != 0.0) tout = fmin(tout, ((dv[c] > 0.0 ? hw[c] : -hw[c]) - o[c]) * rcp_d(dv[c]));
+        att = (float)exp(-a.mu_att * ((sp - s_in) + tout));
+    }
+
     // scattering vector in the lab frame (anisotropic models)
     double qvd[3] = {0.0, 0.0, 0.0};
     if constexpr (kAniso<KIND>) {
@@ -1783,6 +1800,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     }
     float w = (float)(len * a.wscale) * f2;
     if (a.sq_on) w *= struct_factor(a, q);
+    if constexpr (ATT) w *= att;
     if (on_det) {
         ev.pixel = (int32_t)fyp * a.nx + (int32_t)fxp;
         ev.w = w;

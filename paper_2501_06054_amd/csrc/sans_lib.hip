@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const TraceArgs a, LdsLayout l
     }
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += stride) {
-        const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
+        const Event ev = trace_neutron<KIND, MODE, true>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
         if (ev.pixel >= 0) {
             const double w = (double)ev.w;
             __hip_atomic_fetch_add(target + ev.pixel, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void k_debug(const TraceArgs a, LdsLayout l
     __syncthreads();
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.n) return;
-    const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
+    const Event ev = trace_neutron<KIND, MODE, true>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
     if (pixel) pixel[j] = ev.pixel;
     if (w) w[j] = ev.w;
     if (q) q[j] = ev.q;
@@ -1562,6 +1562,9 @@ int validate(const sans_params* p)
         if (!finite(p->sld[k])) return fail(SANS_E_INVALID_ARG, "sld must be finite");
     if (!(p->phi >= 0.0 && p->phi < 1.0)) return fail(SANS_E_INVALID_ARG, "phi must be in [0, 1)");
     if (!(p->sq_phi >= 0.0 && p->sq_phi < 0.6)) return fail(SANS_E_INVALID_ARG, "sq_phi must be in [0, 0.6)");
+    if (!(p->mu_att >= 0.0 && finite(p->mu_att))) return fail(SANS_E_INVALID_ARG, "mu_att must be >= 0");
+    if (p->mu_att > 0.0 && p->mode == SANS_MODE_SURROGATE)
+        return fail(SANS_E_UNSUPPORTED, "surrogate mode: no attenuation");
     if (p->sq_phi > 0.0 && !(p->sq_radius > 0.0)) return fail(SANS_E_INVALID_ARG, "sq_radius must be > 0");
     if (p->sq_kind < SANS_SQ_HARD_SPHERE || p->sq_kind > SANS_SQ_SQUARE_WELL)
         return fail(SANS_E_UNSUPPORTED, "unknown sq_kind");
@@ -1700,6 +1703,8 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     const double sh = std::sin(0.5 * p->cone_alpha);
     *omc = 2.0 * sh * sh;
     a.omc = *omc;
+    a.mu_att = p->mu_att;
+    a.att_on = p->mu_att > 0.0;
     a.det_z = p->det_z;
     a.det_hw = 0.5 * p->det_w;
     a.det_hh = 0.5 * p->det_h;
@@ -2125,8 +2130,9 @@ bool hist_fits(const sans_model_s* m)
 int choose_tally(const sans_model_s* m, bool extras)
 {
     int t = m->p.tally;
-    // the optional sum-of-squares and count outputs use the atomic path
-    if (extras) return t == SANS_TALLY_XCD ? SANS_TALLY_XCD : SANS_TALLY_GLOBAL;
+    // the optional sum-of-squares and count outputs use the atomic path, and
+    // so do attenuated runs (only the atomic-tally kernels carry it)
+    if (extras || m->p.mu_att > 0.0) return t == SANS_TALLY_XCD ? SANS_TALLY_XCD : SANS_TALLY_GLOBAL;
     // the exact average spends thousands of operations per tallied neutron:
     // plain atomics cost nothing there, and the workgroup histogram's LDS
     // would halve the waves per SIMD
@@ -2827,6 +2833,8 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
     double total_n = 0.0;
     for (int e = 0; e < n_exp; ++e) {
         int rc = validate(&p[e]);
+        if (rc == SANS_OK && p[e].mu_att > 0.0)
+            rc = fail(SANS_E_UNSUPPORTED, "batched launch: no attenuation (trace attenuated experiments one by one)");
         if (rc) return rc;
         if (p[e].mode != SANS_MODE_MC) return fail(SANS_E_UNSUPPORTED, "batch: Monte Carlo mode only");
         if (p[e].nx != nx || p[e].ny != ny) return fail(SANS_E_INVALID_ARG, "batch: detectors must match");

@@ -15,7 +15,7 @@ import torch  # loaded first so that libsans shares PyTorch's HIP runtime
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsans.so")
 
-SANS_ABI_VERSION = 4
+SANS_ABI_VERSION = 5
 SANS_OK = 0
 SANS_E_INVALID_ARG = -1
 SANS_E_UNSUPPORTED = -2
@@ -69,7 +69,7 @@ class sans_params(C.Structure):
         ("det_w", C.c_double), ("det_h", C.c_double), ("det_z", C.c_double),
         ("nx", C.c_int32), ("ny", C.c_int32), ("quad_n", C.c_int32), ("tally", C.c_int32),
         ("poly_kind", C.c_int32), ("sq_kind", C.c_int32),
-        ("extra", C.c_double * 4), ("sq_extra", C.c_double * 2),
+        ("extra", C.c_double * 4), ("sq_extra", C.c_double * 2), ("mu_att", C.c_double),
     ]
 
 
@@ -175,6 +175,7 @@ def to_params(p: dict, tally: str = "auto") -> sans_params:
     for k, v in enumerate(p.get("extra", (0.0, 0.0, 0.0, 0.0))):
         s.extra[k] = float(v)
     s.sq_kind = SQ_KIND[p.get("sq_kind", "hard_sphere")]
+    s.mu_att = float(p.get("mu_att", 0.0))
     for k, v in enumerate(p.get("sq_extra", (0.0, 0.0))):
         s.sq_extra[k] = float(v)
     return s

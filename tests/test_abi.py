@@ -197,6 +197,9 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
     (dict(kind="pringle", size=(60.0, 10.0, 0.0), extra=(0.001, 0.02, 0, 0), mode="quad", orient_kind="isotropic"),
      "SANS_E_UNSUPPORTED"),
     (dict(kind="pringle", size=(60.0, 0.0, 0.0), extra=(0.001, 0.02, 0, 0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="sphere", mu_att=-1.0), "SANS_E_INVALID_ARG"),
+    (dict(kind="parallelepiped", size=(20.0, 40.0, 120.0), mode="surrogate", orient_kind="isotropic", mu_att=10.0),
+     "SANS_E_UNSUPPORTED"),
 ])
 def test_capped_body_params_rejected_without_gpu(S, over, code):
     from paper_2501_06054_amd import workloads as W

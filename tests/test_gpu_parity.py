@@ -343,6 +343,10 @@ PER_NEUTRON = {
                                                  sld=(3e-6, 0.5e-6, 6.3e-6), phi=0.25, extra=(0.01, 0, 0, 0)), 30011),
     "adsorbed_layer": (W.params(kind="adsorbed_layer", size=(2000.0, 0, 0), shell=2.5, sld=(1.5e-6, 0, 6.3e-6),
                                 extra=(12.0, 0, 0, 0), phi=0.05), 30011),
+    # sample attenuation
+    "attenuated_coreshell": (dict(W.workload("coreshell_py")["params"], mu_att=150.0), 30011),
+    "attenuated_wide_cone_cylinder": (W.params(kind="cylinder", size=(20.0, 200.0, 0), orient_kind="isotropic",
+                                               cone_alpha=1.0, sample_d=0.003, mu_att=400.0), 30011),
     # pringle (complex amplitude, a polar rule per event)
     "pringle_iso": (W.params(kind="pringle", size=(60.0, 10.0, 0), extra=(0.001, 0.02, 0, 0), quad_n=16,
                              orient_kind="isotropic"), 10011),
@@ -381,7 +385,7 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "mass_surface_fractal", "gel_fit", "sticky_coreshell", "square_well_poly_sphere",
              "oriented_superball", "lamellar_caille", "lamellar_hg", "lamellar_stack_paracrystal",
              "belt_bicelle_gauss", "raspberry_poly", "pearl_necklace", "binary_hard_sphere",
-             "adsorbed_layer", "pringle_iso"]
+             "adsorbed_layer", "pringle_iso", "attenuated_coreshell"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
