@@ -99,6 +99,7 @@ STEP = {
     "belt_F":        ((56,  0,  0, 34, 1, 2), 80),  # belt bicelle: two 2 J1(x)/x, two sinc, roughness exp
     "ads_I":         ((6,   0,  0,  2, 1, 1), 8),   # adsorbed layer: (drho t)^2 exp(-(q sigma)^2) / q^2
     "pr_node":       ((30,  6,  0,  0, 0, 0), 40),  # pringle, one polar node: two sincos, three fma
+    "attenuation":   ((1,   4,  0, 44, 0, 3), 1),   # exit distance (3 axes: quotient, min), FP64 exp, damp
     "weight":        ((3,   0,  0,  2, 0, 0), 3),   # A11
     "detector":      ((0,   5,  0, 23, 0, 1), 0),   # A12: plane crossing (quotient), pixel
     "tally":         ((0,   2,  0,  0, 0, 0), 0),   # A13: address; the add itself is a memory op
@@ -115,6 +116,8 @@ PATHS = {
     "tiny_sphere": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["sphere_F"],
     "coreshell_py": COMMON + ["philox_block"] * 3 + ["uniform"] * 9
                     + ["size_draw", "core_shell_F", "py_sq"],
+    "attenuated_coreshell": COMMON + ["philox_block"] * 3 + ["uniform"] * 9
+                            + ["size_draw", "core_shell_F", "py_sq", "attenuation"],
     "oriented_cylinder": COMMON + ["philox_block"] * 3 + ["uniform"] * 10
                          + ["qvec"] + ["orient_angle"] * 2 + ["project_c", "cylinder_F"],
     "oriented_ellipsoid": COMMON + ["philox_block"] * 3 + ["uniform"] * 11

@@ -403,6 +403,15 @@ def oriented_pringle() -> dict:
                               nx=256, ny=256))
 
 
+def attenuated_coreshell() -> dict:
+    """The core-shell sphere of coreshell_py in a 1 mm slab that attenuates
+    5.6 1/cm (of the order of light water's total cross-section), every
+    neutron damped along its path in and out; 256x256, 1e8 neutrons."""
+    wl = coreshell_py()
+    return dict(name="attenuated_coreshell", n=10**8, seed=34, exp_id=0,
+                params=dict(wl["params"], mu_att=560.0))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -436,6 +445,7 @@ WORKLOADS = {
     "oriented_belt_bicelle": oriented_belt_bicelle,
     "adsorbed_layer": adsorbed_layer,
     "oriented_pringle": oriented_pringle,
+    "attenuated_coreshell": attenuated_coreshell,
 }
 
 
