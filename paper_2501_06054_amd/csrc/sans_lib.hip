@@ -1,17 +1,11 @@
-// sans_lib.hip -- kernels and C ABI of libsans (gfx950).
-//
-// Kernels
-//   k_trace_hist<KIND, MODE>    the hot path for detectors that fit in LDS: one
-//                               neutron per lane, grid-stride over the range,
-//                               FP64 LDS histogram per workgroup
-//   k_emit<KIND, MODE> +        the hot path for larger detectors: events binned
-//   k_bin_accumulate            by detector row band, then summed band by band in LDS
-//   k_trace<KIND, MODE, TALLY>  atomic tallies (global / per-XCD replica)
-//   k_debug<KIND, MODE>         the same per-neutron code, writing (pixel, w, q)
+// sans_lib.hip -- host side of the C ABI of libsans (gfx950), and the small
+// kernels around the per-model ones (sans_kernels.hpp):
+//   k_reduce_partials           sum of the LDS-tally partial histograms
+//   k_bin_accumulate,           binned tally, pass 2: each detector band summed
+//   k_reduce_binned             in LDS, then the bands' slices summed
 //   k_philox                    raw Philox words for stream tests
 //   k_fill, k_sum_replicas      detector clearing / XCD replica reduction
-//   k_pq_avg<KIND>              the exact average <F^2>(q) alone
-// The model switch is a template parameter: a wavefront never diverges on it.
+//   k_schulz_tables             FP64 Schulz quantile tables
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,14 +23,13 @@
 #include "../../include/sans.h"
 #include "sans_device.hpp"
 #include "sans_host_math.hpp"
+#include "sans_kernels.hpp"
 #include "sans_surrogate.hpp"
 
 using namespace sans;
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kXcds = 8;
 constexpr size_t kLdsMax = 160 * 1024;
 
 thread_local std::string g_last_error;
@@ -54,95 +47,6 @@ int fail(int status, const std::string& msg)
             return fail(SANS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
     } while (0)
 
-// ------------------------------------------------------------------ kernels
-
-// Stage an array into LDS with all threads of the block.
-template <typename T>
-__device__ __forceinline__ void stage(T* dst, const T* src, int n)
-{
-    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
-}
-
-// Dynamic LDS, in doubles: [hist (LDS tally only)] [size table] [normal table]
-// [quadrature nodes (floats)]
-struct LdsLayout {
-    int hist, tab_size, tab_norm, quad, total;  // offsets / total in doubles
-    int quad_floats;
-};
-
-struct LdsPtrs {
-    double* hist;
-    double* tsize;
-    double* tnorm;
-    float* lq;
-};
-
-__device__ __forceinline__ LdsPtrs stage_all(const TraceArgs& a, const LdsLayout& lay, double* lds)
-{
-    LdsPtrs p{lds + lay.hist, lds + lay.tab_size, lds + lay.tab_norm,
-              reinterpret_cast<float*>(lds + lay.quad)};
-    if (a.tab_size) stage(p.tsize, a.tab_size, a.M);
-    if (a.tab_norm) stage(p.tnorm, a.tab_norm, a.M);
-    if (lay.quad_floats) stage(p.lq, a.quad_nodes, lay.quad_floats);
-    return p;
-}
-
-// Atomic tallies: one FP64 atomic per detected neutron into the detector
-// (GLOBAL) or into this XCD's replica of it (XCD).
-template <int KIND, int MODE, int TALLY>
-__global__ __launch_bounds__(kBlock) void k_trace(const TraceArgs a, LdsLayout lay, double* det,
-                                                  double* det_w2, unsigned long long* det_cnt,
-                                                  double* replicas)
-{
-    extern __shared__ double lds_d[];
-    const LdsPtrs lp = stage_all(a, lay, lds_d);
-    __syncthreads();
-    double* target = det;
-    if constexpr (TALLY == SANS_TALLY_XCD) {
-        const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kXcds - 1);
-        target = replicas + (size_t)xcc * a.nx * a.ny;
-    }
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += stride) {
-        const Event ev = trace_neutron<KIND, MODE, true>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
-        if (ev.pixel >= 0) {
-            const double w = (double)ev.w;
-            __hip_atomic_fetch_add(target + ev.pixel, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (det_w2)
-                __hip_atomic_fetch_add(det_w2 + ev.pixel, w * w, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            if (det_cnt)
-                __hip_atomic_fetch_add(det_cnt + ev.pixel, 1ull, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-}
-
-// LDS tally: the whole detector as an FP64 histogram in LDS, 1024 lanes per
-// workgroup; each workgroup writes its histogram to its own partial slot
-// (plain stores), summed afterwards by k_reduce_partials.
-constexpr int kHistBlock = 1024;
-
-template <int KIND, int MODE>
-__global__ __launch_bounds__(kHistBlock) void k_trace_hist(const TraceArgs a, LdsLayout lay,
-                                                           double* partial)
-{
-    extern __shared__ double lds_d[];
-    const LdsPtrs lp = stage_all(a, lay, lds_d);
-    const int npix = a.nx * a.ny;
-    for (int i = threadIdx.x; i < npix; i += blockDim.x) lp.hist[i] = 0.0;
-    __syncthreads();
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += stride) {
-        const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
-        if (ev.pixel >= 0)
-            __hip_atomic_fetch_add(lp.hist + ev.pixel, (double)ev.w, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-    __syncthreads();
-    double* out = partial + (size_t)blockIdx.x * npix;
-    for (int i = threadIdx.x; i < npix; i += blockDim.x) out[i] = lp.hist[i];
-}
 
 // det[p] (+)= sum over g < G of partial[g][p]  (p < npix)
 __global__ void k_reduce_partials(double* det, const double* partial, int G, int npix, int accumulate)
@@ -154,58 +58,6 @@ __global__ void k_reduce_partials(double* det, const double* partial, int G, int
     det[p] = accumulate ? det[p] + s : s;
 }
 
-// Binned tally, pass 1: the events of one chunk of neutrons go to the
-// bucket of their detector tile (rows [t*rows, (t+1)*rows)).  Every wave owns
-// one private segment per tile, so no two waves ever write the same
-// counter: ranks come from ballots, and lane t of the wave keeps the running
-// count of tile t in a register (ntiles <= 64).  At the end each wave stores
-// its per-tile counts.  An event is (pixel within the tile, FP32 weight bits).
-constexpr int kEmitBlock = 256;
-constexpr int kMaxTiles = 64;
-
-template <int KIND, int MODE>
-__global__ __launch_bounds__(kEmitBlock) void k_emit(const TraceArgs a, LdsLayout lay, uint2* buckets,
-                                                     unsigned* seg_count, unsigned capw, int tile_pixels,
-                                                     int ntiles)
-{
-    extern __shared__ double lds_d[];
-    const LdsPtrs lp = stage_all(a, lay, lds_d);
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const unsigned nwaves = gridDim.x * (kEmitBlock / 64);
-    const unsigned wv = blockIdx.x * (kEmitBlock / 64) + (threadIdx.x >> 6);
-    unsigned count = 0;  // lane t: events of tile t so far
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j - threadIdx.x < a.n; j += stride) {
-        int t = -1;
-        unsigned local = 0;
-        float w = 0.0f;
-        if (j < a.n) {
-            const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
-            if (ev.pixel >= 0) {
-                t = ev.pixel / tile_pixels;
-                local = (unsigned)(ev.pixel - t * tile_pixels);
-                w = ev.w;
-            }
-        }
-        // one round per distinct tile among the wave's events (wave-uniform
-        // control flow: the tile, its base and the ballots are scalars)
-        uint64_t pending = __ballot(t >= 0);
-        while (pending) {
-            const int tt = __builtin_amdgcn_readlane(t, (int)__builtin_ctzll(pending));
-            const uint64_t same = __ballot(t == tt);
-            const unsigned base = (unsigned)__builtin_amdgcn_readlane((int)count, tt);
-            if (t == tt) {
-                const unsigned rank = base + __builtin_amdgcn_mbcnt_hi((unsigned)(same >> 32),
-                                                                       __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
-                buckets[((size_t)tt * nwaves + wv) * capw + rank] = make_uint2(local, __float_as_uint(w));
-            }
-            if (lane == tt) count += (unsigned)__builtin_popcountll(same);
-            pending &= ~same;
-        }
-    }
-    if (lane < ntiles) seg_count[(size_t)lane * nwaves + wv] = count;
-}
 
 // Binned tally, pass 2: workgroup (t, s) sums the segments of waves
 // [s W/S, (s+1) W/S) of tile t in an LDS histogram of the tile (each of its
@@ -268,20 +120,6 @@ __global__ void k_reduce_binned(double* det, const double* partial, int tile_pix
     det[p] = accumulate ? det[p] + s : s;
 }
 
-template <int KIND, int MODE>
-__global__ __launch_bounds__(kBlock) void k_debug(const TraceArgs a, LdsLayout lay, int32_t* pixel,
-                                                  float* w, float* q)
-{
-    extern __shared__ double lds_d[];
-    const LdsPtrs lp = stage_all(a, lay, lds_d);
-    __syncthreads();
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.n) return;
-    const Event ev = trace_neutron<KIND, MODE, true>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
-    if (pixel) pixel[j] = ev.pixel;
-    if (w) w[j] = ev.w;
-    if (q) q[j] = ev.q;
-}
 
 __global__ void k_philox(uint32_t seed_lo, uint32_t seed_hi, uint64_t first, uint64_t n,
                          uint32_t nblocks, uint32_t exp_id, uint32_t* out)
@@ -331,23 +169,6 @@ __global__ void k_sum_replicas(double* det, double* rep, int npix, int accumulat
     det[i] = s;
 }
 
-template <int KIND>
-__global__ __launch_bounds__(kBlock) void k_pq_avg(const TraceArgs a, LdsLayout lay, const float* q,
-                                                   const float* qvec, int64_t n, float* out)
-{
-    extern __shared__ double lds_d[];
-    (void)stage_all(a, lay, lds_d);
-    __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    float qv[3] = {0.0f, 0.0f, 0.0f};
-    if (qvec) {
-        qv[0] = qvec[3 * j];
-        qv[1] = qvec[3 * j + 1];
-        qv[2] = qvec[3 * j + 2];
-    }
-    out[j] = quad_average<KIND>(a, a.quad_nodes, q[j], qv);
-}
 
 // ------------------------------------------------------------------ Schulz tables (FP64)
 // Quantiles y_k = F^-1((k + 1/2)/M) of the Schulz distribution (Gamma with
@@ -448,289 +269,6 @@ __global__ __launch_bounds__(kSchulzBlock) void k_schulz_tables(const SchulzJob*
     }
 }
 
-// ------------------------------------------------------------------ batched experiments
-// Persistent kernel over a queue of tiles (experiment e, neutron range).
-// Each workgroup pops a tile, stages that experiment's Schulz table into LDS,
-// traces the tile into an LDS histogram of the experiment's detector and
-// adds the histogram to the detector.  The model is uniform per tile, so the
-// switch on it is a scalar branch; every workgroup leaves the loop when the
-// queue is exhausted.
-struct BatchTile {
-    unsigned e;
-    unsigned count;
-    unsigned long long first;
-};
-
-template <int KIND>
-__device__ __forceinline__ void batch_tile(const TraceArgs& a, unsigned long long first, unsigned count,
-                                           double* hist, const double* tab)
-{
-    for (unsigned j = threadIdx.x; j < count; j += blockDim.x) {
-        const Event ev = trace_neutron<KIND, 0>(a, first + j, tab, a.tab_norm, nullptr);
-        if (ev.pixel >= 0)
-            __hip_atomic_fetch_add(hist + ev.pixel, (double)ev.w, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-}
-
-__global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restrict__ exps,
-                                                      const BatchTile* __restrict__ tiles, int ntiles,
-                                                      unsigned* counter, double* dets, int npix, int M)
-{
-    extern __shared__ double lds_d[];
-    double* hist = lds_d;
-    __shared__ int s_tile;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int ti = s_tile;
-        if (ti >= ntiles) break;
-        const BatchTile tl = tiles[ti];
-        const unsigned e = __builtin_amdgcn_readfirstlane(tl.e);
-        const TraceArgs& a = exps[e];
-        for (int i = threadIdx.x; i < npix; i += blockDim.x) hist[i] = 0.0;
-        // the Schulz table stays in global memory (L2/L1): the histogram
-        // takes the workgroup's LDS
-        const double* tab = a.tab_size;
-        __syncthreads();
-        switch (a.kind) {
-        case 0: batch_tile<0>(a, tl.first, tl.count, hist, tab); break;
-        case 1: batch_tile<1>(a, tl.first, tl.count, hist, tab); break;
-        case 2: batch_tile<2>(a, tl.first, tl.count, hist, tab); break;
-        case 3: batch_tile<3>(a, tl.first, tl.count, hist, tab); break;
-        case 4: batch_tile<4>(a, tl.first, tl.count, hist, tab); break;
-        case 5: batch_tile<5>(a, tl.first, tl.count, hist, tab); break;
-        case 6: batch_tile<6>(a, tl.first, tl.count, hist, tab); break;
-        case 7: batch_tile<7>(a, tl.first, tl.count, hist, tab); break;
-        case 8: batch_tile<8>(a, tl.first, tl.count, hist, tab); break;
-        case 9: batch_tile<9>(a, tl.first, tl.count, hist, tab); break;
-        case 10: batch_tile<10>(a, tl.first, tl.count, hist, tab); break;
-        case 11: batch_tile<11>(a, tl.first, tl.count, hist, tab); break;
-        case 12: batch_tile<12>(a, tl.first, tl.count, hist, tab); break;
-        case 13: batch_tile<13>(a, tl.first, tl.count, hist, tab); break;
-        case 14: batch_tile<14>(a, tl.first, tl.count, hist, tab); break;
-        case 15: batch_tile<15>(a, tl.first, tl.count, hist, tab); break;
-        case 16: batch_tile<16>(a, tl.first, tl.count, hist, tab); break;
-        case 17: batch_tile<17>(a, tl.first, tl.count, hist, tab); break;
-        case 18: batch_tile<18>(a, tl.first, tl.count, hist, tab); break;
-        case 19: batch_tile<19>(a, tl.first, tl.count, hist, tab); break;
-        case 20: batch_tile<20>(a, tl.first, tl.count, hist, tab); break;
-        case 21: batch_tile<21>(a, tl.first, tl.count, hist, tab); break;
-        case 22: batch_tile<22>(a, tl.first, tl.count, hist, tab); break;
-        case 23: batch_tile<23>(a, tl.first, tl.count, hist, tab); break;
-        case 24: batch_tile<24>(a, tl.first, tl.count, hist, tab); break;
-        case 25: batch_tile<25>(a, tl.first, tl.count, hist, tab); break;
-        case 26: batch_tile<26>(a, tl.first, tl.count, hist, tab); break;
-        case 27: batch_tile<27>(a, tl.first, tl.count, hist, tab); break;
-        case 28: batch_tile<28>(a, tl.first, tl.count, hist, tab); break;
-        case 29: batch_tile<29>(a, tl.first, tl.count, hist, tab); break;
-        case 30: batch_tile<30>(a, tl.first, tl.count, hist, tab); break;
-        case 31: batch_tile<31>(a, tl.first, tl.count, hist, tab); break;
-        case 32: batch_tile<32>(a, tl.first, tl.count, hist, tab); break;
-        case 33: batch_tile<33>(a, tl.first, tl.count, hist, tab); break;
-        case 34: batch_tile<34>(a, tl.first, tl.count, hist, tab); break;
-        case 35: batch_tile<35>(a, tl.first, tl.count, hist, tab); break;
-        case 36: batch_tile<36>(a, tl.first, tl.count, hist, tab); break;
-        case 37: batch_tile<37>(a, tl.first, tl.count, hist, tab); break;
-        case 38: batch_tile<38>(a, tl.first, tl.count, hist, tab); break;
-        case 39: batch_tile<39>(a, tl.first, tl.count, hist, tab); break;
-        case 40: batch_tile<40>(a, tl.first, tl.count, hist, tab); break;
-        case 41: batch_tile<41>(a, tl.first, tl.count, hist, tab); break;
-        case 42: batch_tile<42>(a, tl.first, tl.count, hist, tab); break;
-        case 43: batch_tile<43>(a, tl.first, tl.count, hist, tab); break;
-        case 44: batch_tile<44>(a, tl.first, tl.count, hist, tab); break;
-        case 45: batch_tile<45>(a, tl.first, tl.count, hist, tab); break;
-        case 46: batch_tile<46>(a, tl.first, tl.count, hist, tab); break;
-        case 47: batch_tile<47>(a, tl.first, tl.count, hist, tab); break;
-        case 48: batch_tile<48>(a, tl.first, tl.count, hist, tab); break;
-        case 49: batch_tile<49>(a, tl.first, tl.count, hist, tab); break;
-        case 50: batch_tile<50>(a, tl.first, tl.count, hist, tab); break;
-        case 51: batch_tile<51>(a, tl.first, tl.count, hist, tab); break;
-        case 52: batch_tile<52>(a, tl.first, tl.count, hist, tab); break;
-        case 53: batch_tile<53>(a, tl.first, tl.count, hist, tab); break;
-        case 54: batch_tile<54>(a, tl.first, tl.count, hist, tab); break;
-        case 55: batch_tile<55>(a, tl.first, tl.count, hist, tab); break;
-        case 56: batch_tile<56>(a, tl.first, tl.count, hist, tab); break;
-        case 57: batch_tile<57>(a, tl.first, tl.count, hist, tab); break;
-        case 58: batch_tile<58>(a, tl.first, tl.count, hist, tab); break;
-        case 59: batch_tile<59>(a, tl.first, tl.count, hist, tab); break;
-        case 60: batch_tile<60>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<61>(a, tl.first, tl.count, hist, tab); break;
-        }
-        __syncthreads();
-        double* det = dets + (size_t)e * npix;
-        for (int i = threadIdx.x; i < npix; i += blockDim.x) {
-            const double v = hist[i];
-            if (v != 0.0) __hip_atomic_fetch_add(det + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();
-    }
-}
-
-// ------------------------------------------------------------------ surrogate mode
-// Rg^2 = (s0^2 + s1^2 + s2^2) / D: D = 12 for the parallelepiped (edges), 5
-// for the ellipsoid (semi-axes).
-__host__ __device__ constexpr double sur_rg2_scale(int kind) { return kind == kParallelepiped ? 1.0 / 12.0 : 1.0 / 5.0; }
-
-// Inputs of the network for one neutron: ln(q s0), ln(s1/s0), ln(s2/s0), p.
-struct SurConst {
-    float ls0;            // ln(size[0])
-    float x1, x2, x3;     // the constant inputs of this model
-    float lo0, hi0;       // domain of ln(q s0)
-    float mid0, scale0;   // normalisation of ln(q s0): (x - mid0) * scale0
-    float f2_0;           // <F^2>(0)
-    float kref;           // Rg^2 / 6 (A^2): P_ref = (1 + q^2 kref)^-2
-};
-
-// Surrogate tracer.  Geometry and S(q) per lane; the network per wave (16
-// samples at a time, activations in registers); in-domain neutrons are
-// tallied with FP64 global atomics, the others queued for the exact pass.
-template <int KIND>
-__global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const mlp::bf16x8* __restrict__ pk,
-                                                      const __bf16* __restrict__ wts, const SurConst sc,
-                                                      double* det, unsigned long long* queue, unsigned* qcount)
-{
-    __shared__ float xs_all[kBlock / 64][64 * mlp::kIn];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float* xs = xs_all[wave];
-    const __amdgpu_buffer_rsrc_t rp = sur::make_rsrc(pk, (int)(16 * sur::kPackTotal));
-    const __amdgpu_buffer_rsrc_t rw = sur::make_rsrc(wts, (int)(2 * sur::kWeightsPadded));
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < a.n; j0 += stride) {
-        const uint64_t j = j0 + threadIdx.x;
-        const bool valid = j < a.n;
-        Event ev{-1, 0.0f, 0.0f};
-        if (valid) ev = trace_neutron<KIND, 2>(a, a.first + j, nullptr, nullptr, nullptr);
-        const float x0 = __logf(ev.q) + sc.ls0;
-        const bool in_dom = valid && ev.pixel >= 0 && x0 >= sc.lo0 && x0 <= sc.hi0;
-        float* xr = xs + lane * mlp::kIn;
-        xr[0] = (fminf(fmaxf(x0, sc.lo0), sc.hi0) - sc.mid0) * sc.scale0;
-        xr[1] = sc.x1;
-        xr[2] = sc.x2;
-        xr[3] = sc.x3;
-        xr[4] = xr[5] = xr[6] = xr[7] = 0.0f;
-        __syncthreads();
-        float y = 0.0f;
-#pragma unroll 1
-        for (int c = 0; c < 4; c += 2) {
-            // the weight loads must not be hoisted out of this loop (they
-            // would occupy hundreds of registers): opaque memory barrier
-            asm volatile("" ::: "memory");
-            float yc[2];
-            sur::forward32(rp, rw, xs, c, yc);
-            if ((lane >> 4) == c) y = yc[0];
-            if ((lane >> 4) == c + 1) y = yc[1];
-        }
-        __syncthreads();
-        if (in_dom) {
-            const float t = __builtin_fmaf(ev.q * ev.q, sc.kref, 1.0f);
-            const double w = (double)(ev.w * sc.f2_0 * __expf(y) * rcpf(t * t));
-            __hip_atomic_fetch_add(det + ev.pixel, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else if (valid && ev.pixel >= 0) {
-            const unsigned slot = atomicAdd(qcount, 1u);
-            queue[slot] = a.first + j;
-        }
-    }
-}
-
-// Exact (quadrature) pass over the queued neutrons: one wave per neutron,
-// its 64 lanes share the quadrature nodes and add their partial weights (the
-// queue holds few neutrons, each costing thousands of node evaluations).
-template <int KIND>
-__global__ __launch_bounds__(kBlock) void k_trace_queue(const TraceArgs a, LdsLayout lay,
-                                                        const unsigned long long* queue, const unsigned* qcount,
-                                                        double* det)
-{
-    extern __shared__ double lds_d[];
-    const LdsPtrs lp = stage_all(a, lay, lds_d);
-    __syncthreads();
-    const unsigned nq = *qcount;
-    const int lane = threadIdx.x & 63;
-    const unsigned waves = gridDim.x * (blockDim.x / 64);
-    for (unsigned i = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); i < nq; i += waves) {
-        const Event ev = trace_neutron<KIND, 1>(a, queue[i], lp.tsize, lp.tnorm, lp.lq, lane, 64);
-        float w = ev.w;
-        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
-        if (lane == 0 && ev.pixel >= 0)
-            __hip_atomic_fetch_add(det + ev.pixel, (double)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// Training targets: for inputs x = (ln(q s0), ln(s1/s0), ln(s2/s0), p, ...)
-// the exact ln(<F^2>(q) / <F^2>(0)) of an isotropically oriented particle
-// with sizes s0 (1, e^x1, e^x2), Schulz width p on all sizes.  Orientation
-// nodes in LDS as in quad_average; size nodes per sample from gx, gw.
-template <int KIND>
-__global__ __launch_bounds__(kBlock) void k_pq_dataset(const TraceArgs a, const float* __restrict__ x,
-                                                       int64_t n, float* __restrict__ out,
-                                                       const float* __restrict__ nodes, int nq, int dims,
-                                                       const double* __restrict__ gl_x,
-                                                       const double* __restrict__ gl_w)
-{
-    __shared__ float lq[5 * kMaxQuad];
-    for (int i = threadIdx.x; i < 5 * nq; i += blockDim.x) lq[i] = nodes[i];
-    __syncthreads();
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n) return;
-    const float* xi = x + idx * mlp::kIn;
-    const float q = __expf(xi[0]);
-    const float s1 = __expf(xi[1]), s2 = __expf(xi[2]);
-    const double pw = xi[3];
-    const float* mu = lq;
-    const float* wmu = lq + nq;
-    const float* cb = lq + 2 * nq;
-    const float* sb = lq + 3 * nq;
-    const float* wb = lq + 4 * nq;
-    const int ny = pw > 0.0 ? nq : 1;
-    double lo = 1.0, hi = 1.0, aa = 0.0, lnorm = 0.0;
-    if (pw > 0.0) {
-        lo = fmax(0.0, 1.0 - 6.0 * pw);
-        hi = 1.0 + 8.0 * pw;
-        aa = 1.0 / (pw * pw);
-        lnorm = aa * log(aa) - lgamma(aa);
-    }
-    double num = 0.0, den = 0.0, wsum = 0.0;
-    for (int j = 0; j < ny; ++j) {
-        double y = 1.0, wy = 1.0;
-        if (pw > 0.0) {
-            y = lo + 0.5 * (hi - lo) * (gl_x[j] + 1.0);
-            wy = y > 0.0 ? gl_w[j] * exp(lnorm + (aa - 1.0) * log(y) - aa * y) : 0.0;
-        }
-        const float s[3] = {(float)y, (float)(s1 * y), (float)(s2 * y)};
-        float avg = 0.0f;
-        if (dims == 1) {
-            for (int i = 0; i < nq; ++i) {
-                const float m = mu[i];
-                const float st = sqrtf(fmaxf(1.0f - m * m, 0.0f));
-                const float f = amplitude_f<KIND>(a, s, q, q * st, 0.0f, q * m, (float)y);
-                avg = __builtin_fmaf(wmu[i], f * f, avg);
-            }
-        } else {
-            for (int i = 0; i < nq; ++i) {
-                const float m = mu[i];
-                const float qst = q * sqrtf(fmaxf(1.0f - m * m, 0.0f));
-                const float qc = q * m;
-                float inner = 0.0f;
-                for (int l = 0; l < nq; ++l) {
-                    const float f = amplitude_f<KIND>(a, s, q, qst * cb[l], qst * sb[l], qc, (float)y);
-                    inner = __builtin_fmaf(wb[l], f * f, inner);
-                }
-                avg = __builtin_fmaf(wmu[i], inner, avg);
-            }
-        }
-        const float f0 = amplitude_f<KIND>(a, s, 0.0f, 0.0f, 0.0f, 0.0f, (float)y);
-        num += wy * (double)avg;
-        den += wy * (double)f0 * (double)f0;
-        wsum += wy;
-    }
-    (void)wsum;
-    // the network's target: ln of the normalised average minus ln P_ref,
-    // P_ref = (1 + (q Rg)^2 / 6)^-2 with the body's Rg^2 (Guinier at small q,
-    // q^-4 at large q), which takes most of the dynamic range off the network
-    const double rg2 = (1.0 + exp(2.0 * (double)xi[1]) + exp(2.0 * (double)xi[2])) * sur_rg2_scale(KIND);
-    out[idx] = (float)(log(num / den) + 2.0 * log1p(exp(2.0 * (double)xi[0]) * rg2 / 6.0));
-}
-
 // ------------------------------------------------------------------ VALU issue-rate probe
 // Eight independent dependency chains per lane of one operation class; the
 // issue cost of each class (relative to an FP32 FMA) weighs the algorithmic
@@ -770,381 +308,51 @@ __global__ __launch_bounds__(256) void k_valu_probe(uint32_t* out, uint32_t seed
     out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = r;
 }
 
-// ------------------------------------------------------------------ dispatch tables
-using TraceFn = void (*)(const TraceArgs, LdsLayout, double*, double*, unsigned long long*, double*);
-using DebugFn = void (*)(const TraceArgs, LdsLayout, int32_t*, float*, float*);
-using PqFn = void (*)(const TraceArgs, LdsLayout, const float*, const float*, int64_t, float*);
-
-template <int K, int M>
-TraceFn trace_fn(int tally)
+// ------------------------------------------------------------------ dispatch table
+// Kernel pointers of every model, filled once by the kind-group translation
+// units.  Callers have validated kind (0 .. kNumKinds - 1); mode 0 selects the
+// Monte Carlo kernels, any other mode the exact-average ones.
+const KindFns* kind_table()
 {
-    return tally == SANS_TALLY_XCD ? (TraceFn)k_trace<K, M, SANS_TALLY_XCD>
-                                   : (TraceFn)k_trace<K, M, SANS_TALLY_GLOBAL>;
+    static KindFns table[kNumKinds];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        fill_kinds_0(table);
+        fill_kinds_1(table);
+        fill_kinds_2(table);
+        fill_kinds_3(table);
+        fill_kinds_4(table);
+        fill_kinds_5(table);
+        fill_kinds_6(table);
+        fill_kinds_7(table);
+    });
+    return table;
 }
+
+bool known_kind(int kind) { return kind >= 0 && kind < kNumKinds; }
 
 TraceFn pick_trace(int kind, int mode, int tally)
 {
-#define SANS_CASE(K)                                                                       \
-    case K:                                                                                \
-        return mode == 0 ? trace_fn<K, 0>(tally) : trace_fn<K, 1>(tally);
-    switch (kind) {
-        SANS_CASE(0)
-        SANS_CASE(1)
-        SANS_CASE(2)
-        SANS_CASE(3)
-        SANS_CASE(4)
-        SANS_CASE(5)
-        SANS_CASE(6)
-        SANS_CASE(7)
-        SANS_CASE(8)
-        SANS_CASE(9)
-        SANS_CASE(10)
-        SANS_CASE(11)
-        SANS_CASE(12)
-        SANS_CASE(13)
-        SANS_CASE(14)
-        SANS_CASE(15)
-        SANS_CASE(16)
-        SANS_CASE(17)
-        SANS_CASE(18)
-        SANS_CASE(19)
-        SANS_CASE(20)
-        SANS_CASE(21)
-        SANS_CASE(22)
-        SANS_CASE(23)
-        SANS_CASE(24)
-        SANS_CASE(25)
-        SANS_CASE(26)
-        SANS_CASE(27)
-        SANS_CASE(28)
-        SANS_CASE(29)
-        SANS_CASE(30)
-        SANS_CASE(31)
-        SANS_CASE(32)
-        SANS_CASE(33)
-        SANS_CASE(34)
-        SANS_CASE(35)
-        SANS_CASE(36)
-        SANS_CASE(37)
-        SANS_CASE(38)
-        SANS_CASE(39)
-        SANS_CASE(40)
-        SANS_CASE(41)
-        SANS_CASE(42)
-        SANS_CASE(43)
-        SANS_CASE(44)
-        SANS_CASE(45)
-        SANS_CASE(46)
-        SANS_CASE(47)
-        SANS_CASE(48)
-        SANS_CASE(49)
-        SANS_CASE(50)
-        SANS_CASE(51)
-        SANS_CASE(52)
-        SANS_CASE(53)
-        SANS_CASE(54)
-        SANS_CASE(55)
-        SANS_CASE(56)
-        SANS_CASE(57)
-        SANS_CASE(58)
-        SANS_CASE(59)
-        SANS_CASE(60)
-        SANS_CASE(61)
-    }
-#undef SANS_CASE
-    return nullptr;
+    return known_kind(kind) ? kind_table()[kind].trace[mode == 0 ? 0 : 1][tally == SANS_TALLY_XCD ? 1 : 0]
+                            : nullptr;
 }
-
-using HistFn = void (*)(const TraceArgs, LdsLayout, double*);
-using EmitFn = void (*)(const TraceArgs, LdsLayout, uint2*, unsigned*, unsigned, int, int);
 
 HistFn pick_hist(int kind, int mode)
 {
-#define SANS_CASE(K)                                                                       \
-    case K:                                                                                \
-        return mode == 0 ? (HistFn)k_trace_hist<K, 0> : (HistFn)k_trace_hist<K, 1>;
-    switch (kind) {
-        SANS_CASE(0)
-        SANS_CASE(1)
-        SANS_CASE(2)
-        SANS_CASE(3)
-        SANS_CASE(4)
-        SANS_CASE(5)
-        SANS_CASE(6)
-        SANS_CASE(7)
-        SANS_CASE(8)
-        SANS_CASE(9)
-        SANS_CASE(10)
-        SANS_CASE(11)
-        SANS_CASE(12)
-        SANS_CASE(13)
-        SANS_CASE(14)
-        SANS_CASE(15)
-        SANS_CASE(16)
-        SANS_CASE(17)
-        SANS_CASE(18)
-        SANS_CASE(19)
-        SANS_CASE(20)
-        SANS_CASE(21)
-        SANS_CASE(22)
-        SANS_CASE(23)
-        SANS_CASE(24)
-        SANS_CASE(25)
-        SANS_CASE(26)
-        SANS_CASE(27)
-        SANS_CASE(28)
-        SANS_CASE(29)
-        SANS_CASE(30)
-        SANS_CASE(31)
-        SANS_CASE(32)
-        SANS_CASE(33)
-        SANS_CASE(34)
-        SANS_CASE(35)
-        SANS_CASE(36)
-        SANS_CASE(37)
-        SANS_CASE(38)
-        SANS_CASE(39)
-        SANS_CASE(40)
-        SANS_CASE(41)
-        SANS_CASE(42)
-        SANS_CASE(43)
-        SANS_CASE(44)
-        SANS_CASE(45)
-        SANS_CASE(46)
-        SANS_CASE(47)
-        SANS_CASE(48)
-        SANS_CASE(49)
-        SANS_CASE(50)
-        SANS_CASE(51)
-        SANS_CASE(52)
-        SANS_CASE(53)
-        SANS_CASE(54)
-        SANS_CASE(55)
-        SANS_CASE(56)
-        SANS_CASE(57)
-        SANS_CASE(58)
-        SANS_CASE(59)
-        SANS_CASE(60)
-        SANS_CASE(61)
-    }
-#undef SANS_CASE
-    return nullptr;
+    return known_kind(kind) ? kind_table()[kind].hist[mode == 0 ? 0 : 1] : nullptr;
 }
 
 EmitFn pick_emit(int kind, int mode)
 {
-#define SANS_CASE(K)                                                                       \
-    case K:                                                                                \
-        return mode == 0 ? (EmitFn)k_emit<K, 0> : (EmitFn)k_emit<K, 1>;
-    switch (kind) {
-        SANS_CASE(0)
-        SANS_CASE(1)
-        SANS_CASE(2)
-        SANS_CASE(3)
-        SANS_CASE(4)
-        SANS_CASE(5)
-        SANS_CASE(6)
-        SANS_CASE(7)
-        SANS_CASE(8)
-        SANS_CASE(9)
-        SANS_CASE(10)
-        SANS_CASE(11)
-        SANS_CASE(12)
-        SANS_CASE(13)
-        SANS_CASE(14)
-        SANS_CASE(15)
-        SANS_CASE(16)
-        SANS_CASE(17)
-        SANS_CASE(18)
-        SANS_CASE(19)
-        SANS_CASE(20)
-        SANS_CASE(21)
-        SANS_CASE(22)
-        SANS_CASE(23)
-        SANS_CASE(24)
-        SANS_CASE(25)
-        SANS_CASE(26)
-        SANS_CASE(27)
-        SANS_CASE(28)
-        SANS_CASE(29)
-        SANS_CASE(30)
-        SANS_CASE(31)
-        SANS_CASE(32)
-        SANS_CASE(33)
-        SANS_CASE(34)
-        SANS_CASE(35)
-        SANS_CASE(36)
-        SANS_CASE(37)
-        SANS_CASE(38)
-        SANS_CASE(39)
-        SANS_CASE(40)
-        SANS_CASE(41)
-        SANS_CASE(42)
-        SANS_CASE(43)
-        SANS_CASE(44)
-        SANS_CASE(45)
-        SANS_CASE(46)
-        SANS_CASE(47)
-        SANS_CASE(48)
-        SANS_CASE(49)
-        SANS_CASE(50)
-        SANS_CASE(51)
-        SANS_CASE(52)
-        SANS_CASE(53)
-        SANS_CASE(54)
-        SANS_CASE(55)
-        SANS_CASE(56)
-        SANS_CASE(57)
-        SANS_CASE(58)
-        SANS_CASE(59)
-        SANS_CASE(60)
-        SANS_CASE(61)
-    }
-#undef SANS_CASE
-    return nullptr;
+    return known_kind(kind) ? kind_table()[kind].emit[mode == 0 ? 0 : 1] : nullptr;
 }
 
 DebugFn pick_debug(int kind, int mode)
 {
-#define SANS_CASE(K)                                                                       \
-    case K:                                                                                \
-        return mode == 0 ? (DebugFn)k_debug<K, 0> : (DebugFn)k_debug<K, 1>;
-    switch (kind) {
-        SANS_CASE(0)
-        SANS_CASE(1)
-        SANS_CASE(2)
-        SANS_CASE(3)
-        SANS_CASE(4)
-        SANS_CASE(5)
-        SANS_CASE(6)
-        SANS_CASE(7)
-        SANS_CASE(8)
-        SANS_CASE(9)
-        SANS_CASE(10)
-        SANS_CASE(11)
-        SANS_CASE(12)
-        SANS_CASE(13)
-        SANS_CASE(14)
-        SANS_CASE(15)
-        SANS_CASE(16)
-        SANS_CASE(17)
-        SANS_CASE(18)
-        SANS_CASE(19)
-        SANS_CASE(20)
-        SANS_CASE(21)
-        SANS_CASE(22)
-        SANS_CASE(23)
-        SANS_CASE(24)
-        SANS_CASE(25)
-        SANS_CASE(26)
-        SANS_CASE(27)
-        SANS_CASE(28)
-        SANS_CASE(29)
-        SANS_CASE(30)
-        SANS_CASE(31)
-        SANS_CASE(32)
-        SANS_CASE(33)
-        SANS_CASE(34)
-        SANS_CASE(35)
-        SANS_CASE(36)
-        SANS_CASE(37)
-        SANS_CASE(38)
-        SANS_CASE(39)
-        SANS_CASE(40)
-        SANS_CASE(41)
-        SANS_CASE(42)
-        SANS_CASE(43)
-        SANS_CASE(44)
-        SANS_CASE(45)
-        SANS_CASE(46)
-        SANS_CASE(47)
-        SANS_CASE(48)
-        SANS_CASE(49)
-        SANS_CASE(50)
-        SANS_CASE(51)
-        SANS_CASE(52)
-        SANS_CASE(53)
-        SANS_CASE(54)
-        SANS_CASE(55)
-        SANS_CASE(56)
-        SANS_CASE(57)
-        SANS_CASE(58)
-        SANS_CASE(59)
-        SANS_CASE(60)
-        SANS_CASE(61)
-    }
-#undef SANS_CASE
-    return nullptr;
+    return known_kind(kind) ? kind_table()[kind].debug[mode == 0 ? 0 : 1] : nullptr;
 }
 
-PqFn pick_pq(int kind)
-{
-    switch (kind) {
-    case 0: return k_pq_avg<0>;
-    case 1: return k_pq_avg<1>;
-    case 2: return k_pq_avg<2>;
-    case 3: return k_pq_avg<3>;
-    case 4: return k_pq_avg<4>;
-    case 5: return k_pq_avg<5>;
-    case 6: return k_pq_avg<6>;
-    case 7: return k_pq_avg<7>;
-    case 8: return k_pq_avg<8>;
-    case 9: return k_pq_avg<9>;
-    case 10: return k_pq_avg<10>;
-    case 11: return k_pq_avg<11>;
-    case 12: return k_pq_avg<12>;
-    case 13: return k_pq_avg<13>;
-    case 14: return k_pq_avg<14>;
-    case 15: return k_pq_avg<15>;
-    case 16: return k_pq_avg<16>;
-    case 17: return k_pq_avg<17>;
-    case 18: return k_pq_avg<18>;
-    case 19: return k_pq_avg<19>;
-    case 20: return k_pq_avg<20>;
-    case 21: return k_pq_avg<21>;
-    case 22: return k_pq_avg<22>;
-    case 23: return k_pq_avg<23>;
-    case 24: return k_pq_avg<24>;
-    case 25: return k_pq_avg<25>;
-    case 26: return k_pq_avg<26>;
-    case 27: return k_pq_avg<27>;
-    case 28: return k_pq_avg<28>;
-    case 29: return k_pq_avg<29>;
-    case 30: return k_pq_avg<30>;
-    case 31: return k_pq_avg<31>;
-    case 32: return k_pq_avg<32>;
-    case 33: return k_pq_avg<33>;
-    case 34: return k_pq_avg<34>;
-    case 35: return k_pq_avg<35>;
-    case 36: return k_pq_avg<36>;
-    case 37: return k_pq_avg<37>;
-    case 38: return k_pq_avg<38>;
-    case 39: return k_pq_avg<39>;
-    case 40: return k_pq_avg<40>;
-    case 41: return k_pq_avg<41>;
-    case 42: return k_pq_avg<42>;
-    case 43: return k_pq_avg<43>;
-    case 44: return k_pq_avg<44>;
-    case 45: return k_pq_avg<45>;
-    case 46: return k_pq_avg<46>;
-    case 47: return k_pq_avg<47>;
-    case 48: return k_pq_avg<48>;
-    case 49: return k_pq_avg<49>;
-    case 50: return k_pq_avg<50>;
-    case 51: return k_pq_avg<51>;
-    case 52: return k_pq_avg<52>;
-    case 53: return k_pq_avg<53>;
-    case 54: return k_pq_avg<54>;
-    case 55: return k_pq_avg<55>;
-    case 56: return k_pq_avg<56>;
-    case 57: return k_pq_avg<57>;
-    case 58: return k_pq_avg<58>;
-    case 59: return k_pq_avg<59>;
-    case 60: return k_pq_avg<60>;
-    case 61: return k_pq_avg<61>;
-    }
-    return nullptr;
-}
+PqFn pick_pq(int kind) { return known_kind(kind) ? kind_table()[kind].pq : nullptr; }
 
 }  // namespace
 
@@ -2234,17 +1442,10 @@ int run_surrogate(sans_model_s* m, const TraceArgs& a, const SurConst& sc, doubl
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, m->d_qcount, 1);
         const uint64_t blocks = (ac.n + kBlock - 1) / kBlock;
         const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)m->num_cu * 8));
-        if (m->p.kind == SANS_PARALLELEPIPED) {
-            hipLaunchKernelGGL(k_trace_sur<kParallelepiped>, dim3(grid), dim3(kBlock), 0, s, ac, m->d_sur_pack,
-                               m->d_sur_w, sc, det, m->d_queue, m->d_qcount);
-            hipLaunchKernelGGL(k_trace_queue<kParallelepiped>, dim3((unsigned)m->num_cu * 2), dim3(kBlock), shmem, s,
-                               ac, lay, m->d_queue, m->d_qcount, det);
-        } else {
-            hipLaunchKernelGGL(k_trace_sur<kEllipsoid>, dim3(grid), dim3(kBlock), 0, s, ac, m->d_sur_pack,
-                               m->d_sur_w, sc, det, m->d_queue, m->d_qcount);
-            hipLaunchKernelGGL(k_trace_queue<kEllipsoid>, dim3((unsigned)m->num_cu * 2), dim3(kBlock), shmem, s,
-                               ac, lay, m->d_queue, m->d_qcount, det);
-        }
+        hipLaunchKernelGGL(sur_kernel(m->p.kind), dim3(grid), dim3(kBlock), 0, s, ac, m->d_sur_pack, m->d_sur_w,
+                           sc, det, m->d_queue, m->d_qcount);
+        hipLaunchKernelGGL(sur_queue_kernel(m->p.kind), dim3((unsigned)m->num_cu * 2), dim3(kBlock), shmem, s,
+                           ac, lay, m->d_queue, m->d_qcount, det);
         HIP_TRY(hipGetLastError());
     }
     return SANS_OK;
@@ -2642,12 +1843,8 @@ int sans_pq_dataset(int32_t kind, const float* x, int64_t n, float* out, int32_t
         a.contrast = 1.0f;
         a.poly_mask = 7;
         const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
-        if (kind == SANS_PARALLELEPIPED)
-            hipLaunchKernelGGL(k_pq_dataset<kParallelepiped>, dim3(grid), dim3(kBlock), 0, s, a, x, n, out, d_nodes,
-                               nq, 2, d_gl, d_gl + nq);
-        else
-            hipLaunchKernelGGL(k_pq_dataset<kEllipsoid>, dim3(grid), dim3(kBlock), 0, s, a, x, n, out, d_nodes, nq,
-                               1, d_gl, d_gl + nq);
+        hipLaunchKernelGGL(dataset_kernel(kind), dim3(grid), dim3(kBlock), 0, s, a, x, n, out, d_nodes, nq,
+                           kind == SANS_PARALLELEPIPED ? 2 : 1, d_gl, d_gl + nq);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -2805,7 +2002,7 @@ int run_batch(BatchCache& c, int n_exp, const std::vector<TraceArgs>& exps,
                                c.cap_stream, c.d_jobs, M, c.d_tables, gl16_nodes());
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, c.cap_stream, c.d_counter, 1);
         const unsigned grid = (unsigned)std::max(1, std::min(ntiles, num_cu));
-        hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kHistBlock), lds, c.cap_stream, c.d_exps, c.d_tiles,
+        hipLaunchKernelGGL(batch_kernel(), dim3(grid), dim3(kHistBlock), lds, c.cap_stream, c.d_exps, c.d_tiles,
                            ntiles, c.d_counter, dets, npix, M);
         hipError_t le = hipGetLastError();
         hipError_t ee = hipStreamEndCapture(c.cap_stream, &c.graph);
@@ -2914,7 +2111,7 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
     if (!host_tabs.empty())
         HIP_TRY(hipMemcpyAsync(c.d_tables + n_schulz * (size_t)M, host_tabs.data(), sizeof(double) * host_tabs.size(),
                                hipMemcpyHostToDevice, s));
-    if ((rc = set_lds_limit((const void*)k_batch, lds))) return rc;
+    if ((rc = set_lds_limit((const void*)batch_kernel(), lds))) return rc;
 
     // tile size: tuning cache, else autotune (when a cache path is given), else default
     const std::string key = tune_key(n_exp, total_n, nx, ny, num_cu);
