@@ -2127,7 +2127,8 @@ static double surrogate_f2(const orc_params* p, double q, int* in_domain)
     double x[4] = {log(q * p->size[0]), log(p->size[1] / p->size[0]), log(p->size[2] / p->size[0]), p->poly};
     *in_domain = 0;
     if (!g_sur_set) return 0.0;
-    if (p->poly_kind != 0 && p->poly > 0.0) return 0.0;   /* trained on Schulz sizes only */
+    /* trained on Schulz sizes that scale all three axes together only */
+    if (p->poly > 0.0 && (p->poly_kind != 0 || (p->poly_mask & 7) != 7)) return 0.0;
     double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < 4; ++k) {
         if (!(x[k] >= g_sur_lo[k] - (k ? 1e-6 : 0.0) && x[k] <= g_sur_hi[k] + (k ? 1e-6 : 0.0))) return 0.0;

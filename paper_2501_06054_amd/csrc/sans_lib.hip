@@ -1400,8 +1400,10 @@ int launch_fill(double* p, size_t n, hipStream_t s)
 bool surrogate_inputs(const sans_model_s* m, SurConst& sc)
 {
     const sans_params& p = m->p;
-    // the networks are trained on Schulz size distributions only
-    if (p.poly > 0.0 && p.poly_kind != SANS_POLY_SCHULZ) return false;
+    // the networks are trained on Schulz size distributions that scale all
+    // three sizes together: any other size distribution takes the exact
+    // average throughout
+    if (p.poly > 0.0 && (p.poly_kind != SANS_POLY_SCHULZ || (p.poly_mask & 7) != 7)) return false;
     const double x[4] = {0.0, std::log(p.size[1] / p.size[0]), std::log(p.size[2] / p.size[0]), p.poly};
     float u[4];
     for (int k = 1; k < 4; ++k) {
