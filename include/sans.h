@@ -429,6 +429,25 @@ int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uin
                   uint32_t flags, double* det, double* det_w2, uint64_t* det_count,
                   void* stream);
 
+/* The same trace as sans_trace_ex without det_w2/det_count, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): it calls no hipMalloc,
+ * hipFree or allocating library routine.  The handle must have been created
+ * beforehand (sans_model_create allocates its tables).  The tally goes
+ * through eight per-XCD FP64 replicas of the detector held in a fixed device
+ * array inside the library (16 MiB on every GPU the library runs on, kept
+ * until the process ends), cleared by each call and summed into det.
+ *   det    device FP64 [ny][nx], caller-owned; overwritten, or added to with
+ *          SANS_ACCUMULATE (the only flag)
+ * Errors: SANS_E_INVALID_ARG for NULL pointers, unknown flags, an overflowing
+ * neutron range or a detector of more than 262144 (512 x 512) pixels;
+ * SANS_E_UNSUPPORTED in SANS_MODE_SURROGATE (its fallback queue is allocated).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams or threads) race and give wrong detectors; serialise
+ * them.  n = 0 only clears det (unless accumulating). */
+int sans_trace_noalloc(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed,
+                       uint32_t exp_id, uint32_t flags, double* det, void* stream);
+
 /* Per-neutron outputs for neutrons first .. first+n-1, computed by the same
  * device code as the tally kernels: pixel (device int32, -1 = not tallied),
  * w (device float, 0 when not tallied) and q = |Q| (device float, 0 when the

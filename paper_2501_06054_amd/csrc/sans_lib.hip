@@ -1453,6 +1453,41 @@ int run_surrogate(sans_model_s* m, const TraceArgs& a, const SurConst& sc, doubl
     return SANS_OK;
 }
 
+// Scratch of sans_trace_noalloc: the eight per-XCD replicas of the detector,
+// in a device array of fixed size that the code object brings with it (every
+// GPU the library runs on holds its own copy until the process ends), so the
+// entry point needs no allocation.  Host code never passes the array's name to
+// a kernel: that is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocMaxPixels = (size_t)1 << 18;            // 512 x 512
+static __device__ __align__(256) double scratch[kNoAllocMaxPixels * kXcds];   // 16 MiB
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on the first call on
+// that device).
+int noalloc_scratch(double** out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SANS_E_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(SANS_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SANS_OK;
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
@@ -1656,6 +1691,49 @@ int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uin
                            (int)npix, 1);
         HIP_TRY(hipGetLastError());
     }
+    return SANS_OK;
+}
+
+int sans_trace_noalloc(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
+                       uint32_t flags, double* det, void* stream)
+{
+    (void)hipGetLastError();  // a stale error of an earlier call is not ours
+    if (!m || !det) return fail(SANS_E_INVALID_ARG, "model or detector is NULL");
+    if (flags & ~SANS_ACCUMULATE) return fail(SANS_E_INVALID_ARG, "unknown flags");
+    if (n > 0 && first + n < first) return fail(SANS_E_INVALID_ARG, "neutron range overflows");
+    if (m->p.mode == SANS_MODE_SURROGATE)
+        return fail(SANS_E_UNSUPPORTED, "sans_trace_noalloc: surrogate mode keeps a queue it allocates");
+    const size_t npix = (size_t)m->p.nx * m->p.ny;
+    if (npix > kNoAllocMaxPixels)
+        return fail(SANS_E_INVALID_ARG, "sans_trace_noalloc: detector of " + std::to_string(npix) +
+                                            " pixels exceeds the limit of " + std::to_string(kNoAllocMaxPixels));
+    double* rep = nullptr;
+    int rc = noalloc_scratch(&rep);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const bool acc = flags & SANS_ACCUMULATE;
+    if (!acc && (rc = launch_fill(det, npix, s))) return rc;
+    if (n == 0) return SANS_OK;
+    // the previous call on this device may have left anything here
+    if ((rc = launch_fill(rep, npix * kXcds, s))) return rc;
+    TraceArgs a = m->args;
+    a.first = first;
+    a.n = n;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    a.exp_id = exp_id;
+    const LdsLayout lay = layout(m, false);
+    const size_t shmem = lds_bytes(lay);
+    TraceFn fn = pick_trace(m->p.kind, m->p.mode, SANS_TALLY_XCD);
+    if (!fn) return fail(SANS_E_UNSUPPORTED, "no kernel for this model");
+    if ((rc = set_lds_limit((const void*)fn, shmem))) return rc;
+    const uint64_t blocks_needed = (n + kBlock - 1) / kBlock;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks_needed, (uint64_t)m->num_cu * 8));
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), shmem, s, a, lay, det, (double*)nullptr,
+                       (unsigned long long*)nullptr, rep);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_replicas, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, det, rep, (int)npix, 1);
+    HIP_TRY(hipGetLastError());
     return SANS_OK;
 }
 

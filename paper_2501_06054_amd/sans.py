@@ -84,6 +84,7 @@ def _load():
     L.sans_model_destroy.argtypes = [vp]
     L.sans_trace.argtypes = [vp, u64, u64, P(sans_params), vp, vp]
     L.sans_trace_ex.argtypes = [vp, u64, u64, u64, u32, u32, vp, vp, vp, vp]
+    L.sans_trace_noalloc.argtypes = [vp, u64, u64, u64, u32, u32, vp, vp]
     L.sans_debug_trace.argtypes = [vp, u64, u64, u64, u32, vp, vp, vp, vp]
     L.sans_debug_philox.argtypes = [u64, u64, u64, u32, u32, vp, vp]
     L.sans_debug_table.argtypes = [vp, i32, P(C.c_double), i32]
@@ -115,7 +116,7 @@ def _load():
     L.sans_status_string.argtypes = [C.c_int]
     L.sans_status_string.restype = C.c_char_p
     L.sans_last_error.restype = C.c_char_p
-    for f in ("sans_model_create", "sans_model_destroy", "sans_trace", "sans_trace_ex",
+    for f in ("sans_model_create", "sans_model_destroy", "sans_trace", "sans_trace_ex", "sans_trace_noalloc",
               "sans_debug_trace", "sans_debug_philox", "sans_debug_table", "sans_debug_weight_scale", "sans_pq_avg",
               "sans_model_constants", "sans_trace_batch", "sans_batch_release"):
         getattr(L, f).restype = C.c_int
@@ -209,6 +210,12 @@ def sans_trace_ex(h, first: int, n: int, seed: int, exp_id: int, flags: int, det
                              _dev(det_w2, torch.float64, "det_w2"),
                              _dev(det_count, torch.int64, "det_count"), _stream(stream)),
            "sans_trace_ex")
+
+
+def sans_trace_noalloc(h, first: int, n: int, seed: int, exp_id: int, flags: int, det,
+                       stream=None) -> None:
+    _check(lib.sans_trace_noalloc(h, first, n, seed, exp_id, flags, _dev(det, torch.float64, "det"),
+                                  _stream(stream)), "sans_trace_noalloc")
 
 
 def sans_debug_trace(h, first: int, n: int, seed: int, exp_id: int, pixel=None, w=None, q=None,
