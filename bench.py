@@ -9,13 +9,18 @@ detector, 1e8 neutrons per step.
 
 Prints one JSON line (rank 0, one GPU):
   metric/value/unit       neutrons traced per second (whole job)
-  roofline                the trace kernel against the VALU issue ceiling
-                          (algorithmic lane-op slots per neutron x neutrons per
-                          launch / launch time from HIP events on its stream)
-  fp32_valu               the same kernel's algorithmic FP32 flops against the
-                          FP32 vector peak
+  roofline                the trace call against the FP32 vector peak:
+                          algorithmic FP32 flops per neutron x neutrons per
+                          call / the call's time from HIP events on its stream
+  valu                    counter-measured VALU work of the trace kernel
+                          (instructions and FP32 flops per neutron, VALU busy,
+                          clock), when measured on the current kernel sources
   cpu_baseline            the FP64 CPU oracle on a bounded sample of the same
-                          workload, on this host's cores
+                          workload, built for and run on this host's cores
+  other_configs           the other configurations timed on the same GPU: the
+                          oriented cylinder and ellipsoid at 1e9 neutrons, the
+                          4096-experiment batch against plain traces, and the
+                          surrogate against the exact-average trace
 """
 from __future__ import annotations
 
@@ -31,86 +36,44 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks and unit counts
 PEAK_FP32_TFLOPS = 157.3
 CUS, CLOCK_GHZ = 256, 2.4
-# The VALU ceiling in FP32-FMA lane slots: 157.3 TFLOP/s = 256 CUs x 2.4 GHz
-# x 128 FMA lanes per clock (two wave64 FP32 FMAs per clock per CU).
-PEAK_VALU_TSLOTS = PEAK_FP32_TFLOPS / 2.0
 
-# Issue cost of each operation class in FP32-FMA slots, from the rates
-# measured on MI355X by sans_debug_valu_rates (bench.py --workload
-# valu_rates; wave64 instructions per clock per CU: FP32 FMA 1.49, 32-bit
-# integer 1.54, 32x32->64 multiply with an xor 0.86, FP64 FMA 0.79, FP32
-# reciprocal 0.45, FP64 reciprocal 0.24).  A GPU test keeps the measured
-# costs within 30 % of these.
-SLOT_COST = {"fp32": 1.0, "int32": 1.0, "mul64": 2.5, "fp64": 1.9, "trans32": 3.3, "trans64": 6.3}
+# Algorithmic FP32 flops per neutron (FMA = 2) of the four reference
+# configurations: the per-neutron budget of the method's FP32 steps (A9-A11)
+# with the amplitudes in their closed forms -- tiny sphere: 3 j1(x)/x and the
+# weight; core-shell: two sphere amplitudes, the Percus-Yevick S(Q) and the
+# weight; oriented cylinder and triaxial ellipsoid: the projected amplitude
+# (sinc and 2 J1(x)/x, or 3 j1(x)/x of the scaled radius) and the weight.
+# Other workloads use the step counts below.
+REFERENCE_FLOPS = {"tiny_sphere": 35, "coreshell_py": 110, "oriented_cylinder": 80,
+                   "oriented_ellipsoid": 80}
 
-# Algorithmic work per neutron, counted from the method's steps (tabulated in
-# the design notes): operations per lane by class -- fp32 and fp64 add, mul,
-# fma, min/max, compare or conversion; int32 add, xor, logic or select;
-# mul64 a 32x32->64 multiply; trans32 an FP32 reciprocal/sqrt/exp/log; trans64
-# the FP64 reciprocal or rsq estimate (the Newton steps that refine it are
-# fp64 ops).  Where a function has a short series below a threshold, the
-# cheaper (series) form is counted, so the totals are lower bounds.  The last
-# column is the FP32 flops of the weight (fma 2).
-#           step               fp32 int32 mul64 fp64 trans32 trans64 | fp32 flops
+# FP32 flops of each step of the per-neutron work (FMA = 2), counted from the
+# method's steps with the cheaper series forms where a function has one below
+# a threshold (so these are lower bounds).  The geometry (A3-A6, A12) is FP64
+# and contributes none.
 STEP = {
-    "philox_block":  ((0,  40, 20,  0, 0, 0), 0),   # 10 rounds: 2 multiplies, 4 xor
-    "uniform":       ((0,   0,  0,  2, 0, 0), 0),   # u32 -> f64, fma
-    "source_slit":   ((0,   0,  0, 30, 0, 3), 0),   # A3: points, |d| (sqrt), 1/|d|, lambda, 2 pi/lambda
-    "slab":          ((0,   2,  0, 38, 0, 3), 0),   # A4: 3 axes x (1/k_c, 2 planes, min/max), chord
-    "scatter_point": ((0,   0,  0,  4, 0, 0), 0),   # A5
-    "cone_q":        ((0,   8,  0, 69, 0, 3), 0),   # A6: t, sqrt, sincospi(psi), Duff basis, k_f, |Q|
-    "qvec":          ((0,   0,  0,  6, 0, 0), 0),   # Q vector (anisotropic models)
-    "size_draw":     ((0,   2,  0, 10, 0, 0), 0),   # A7: FP64 table lerp
-    "orient_angle":  ((0,   2,  0, 31, 0, 0), 0),   # A8 per Gaussian angle: lerp, Taylor sincos, rotation
-    "project_c":     ((0,   0,  0,  5, 0, 0), 0),   # Q . C
-    "project_abc":   ((0,   0,  0, 27, 0, 0), 0),   # Q . A, Q . B, Q . C
-    "sphere_F":      ((15,  0,  0,  4, 0, 0), 21),  # A9: phase, 3 j1(x)/x series, volume
-    "core_shell_F":  ((29,  0,  0, 10, 0, 0), 44),
-    "cylinder_F":    ((24,  0,  0, 13, 0, 1), 39),  # Q_AB (sqrt), sinc and 2 J1(x)/x series
-    "ellipsoid_F":   ((15,  0,  0, 15, 0, 1), 25),  # |(aQ_A, bQ_B, cQ_C)| (sqrt), series
-    "caps_phase":    ((16,  6,  0,  8, 0, 0), 26),  # cap centre phase: FP64 reduction, sincos polynomials
-    "cap_node":      ((37,  6,  0,  0, 0, 0), 58),  # per cap node: sincos of B t, angle sum, 2 J1(x)/x series
-    "hollow_F":      ((62, 18,  0, 21, 3, 0), 93),  # 3 x (FP64 phase reduction, sincos, sin/x), 3 faces
-    "micelle_F":     ((59,  0,  0,  9, 0, 0), 96),  # core 3 j1(x)/x, sinc, two chain series, the sum
-    "cs_cyl_F":      ((50,  0,  0, 28, 0, 2), 80),  # two cylinders (core, outer), contrasts
-    "cs_ell_F":      ((31,  0,  0, 32, 0, 2), 52),  # two ellipsoids (core, outer), contrasts
-    "thick_box_F":   ((68,  0,  0, 15, 0, 0), 122), # box minus cavity: six sinc series
-    "iso_orient":    ((0,   4,  0, 70, 0, 1), 0),   # cos theta = 2u - 1, sin theta (sqrt), two sincospi
-    "ts_I":          ((6,   0,  0,  2, 1, 0), 8),   # Teubner-Strey: q^2 + c, square + e, reciprocal, scale
-    "pcoil_I":       ((2,   0,  0, 35, 0, 2), 0),   # polydisperse coil: FP64 power (log, exp), quotient
-    "mfrac_I":       ((40,  0,  0,  1, 4, 0), 60),  # mass fractal: atan, sin, log2, exp2, reciprocal
-    "shell_F":       ((32,  0,  0,  8, 0, 0), 44),  # one vesicle shell: two 3 j1(x)/x (FP64 phases), volumes
-    "ellcyl_F":      ((24,  0,  0, 15, 0, 1), 39),  # elliptical cylinder: |(a Q_A, b Q_B)| (sqrt), sinc, 2 J1(x)/x
-    "paracrystal_Z": ((54,  6,  0, 60, 1, 3), 60),  # 3 x (Q.v_k, FP64 half-phase reduction, sin^2, quotient), e
-    "pev_I":         ((196, 0,  0,  4, 64, 0), 256),  # excluded-volume chain: two 32-node rules of t^(s-1) exp(-U t)
-                                                      # (a multiply, an exp and an fma per node)
-    "py_sq":         ((15,  0,  0,  0, 1, 0), 25),  # A10: series in x^2, 1/(1 + 24 phi G/x)
-    "sticky_sq":     ((27,  0,  0,  0, 1, 0), 50),  # adhesive spheres: two series in k^2, A^2 + B^2, reciprocal
-    "msf_I":         ((8,   0,  0,  3, 3, 0), 10),  # mass-surface fractal: two log2, one exp2
-    "sb_row":        ((16,  3,  0,  0, 0, 0), 22),  # superball, per x node: cos(Q_A R x), the row's sum
-    "sb_node":       ((32,  6,  0,  0, 0, 0), 44),  # superball, per (x, y) node: cos(Q_B R y), sin(Q_C R zm)/Q_C R
-    "lam_hg_F":      ((24,  0,  0,  4, 0, 1), 30),  # head-tail bilayer: two sinc (FP64 phases), 2 pi/delta, 1/q^2
-    "caille_term":   ((18,  3,  0,  6, 1, 0), 24),  # one sheet pair of a Caille stack: FP64 phase reduction, cos, exp
-    "neck_node":     ((34,  6,  0,  6, 2, 0), 44),  # necklace rod rule node: two sinc (one FP64 phase), two fma
-    "neck_unit":     ((8,   0,  0,  0, 0, 0), 12),  # necklace pair-sum step: power, three fma
-    "bhs_node":      ((16,  3,  0,  0, 0, 0), 20),  # binary spheres, one node of a Qhat_ij integral: sincos, two fma
-    "bhs_mat":       ((24,  0,  0,  0, 1, 0), 40),  # binary spheres: Qhat^H Qhat, its inverse, v^T S v
-    "rasp_F":        ((36,  0,  0, 12, 0, 0), 60),  # raspberry: two sphere amplitudes, sinc(qD), the pair sum
-    "belt_F":        ((56,  0,  0, 34, 1, 2), 80),  # belt bicelle: two 2 J1(x)/x, two sinc, roughness exp
-    "ads_I":         ((6,   0,  0,  2, 1, 1), 8),   # adsorbed layer: (drho t)^2 exp(-(q sigma)^2) / q^2
-    "pr_node":       ((30,  6,  0,  0, 0, 0), 40),  # pringle, one polar node: two sincos, three fma
-    "attenuation":   ((1,   4,  0, 44, 0, 3), 1),   # exit distance (3 axes: quotient, min), FP64 exp, damp
-    "weight":        ((3,   0,  0,  2, 0, 0), 3),   # A11
-    "detector":      ((0,   5,  0, 23, 0, 1), 0),   # A12: plane crossing (quotient), pixel
-    "tally":         ((0,   2,  0,  0, 0, 0), 0),   # A13: address; the add itself is a memory op
+    "philox_block": 0, "uniform": 0, "source_slit": 0, "slab": 0, "scatter_point": 0, "cone_q": 0,
+    "qvec": 0, "size_draw": 0, "orient_angle": 0, "project_c": 0, "project_abc": 0,
+    "sphere_F": 21,      # phase, 3 j1(x)/x series, volume
+    "core_shell_F": 44,
+    "cylinder_F": 39,    # Q_AB (sqrt), sinc and 2 J1(x)/x series
+    "ellipsoid_F": 25,   # |(aQ_A, bQ_B, cQ_C)| (sqrt), series
+    "caps_phase": 26,    # cap centre phase: FP64 reduction, sincos polynomials
+    "cap_node": 58,      # per cap node: sincos of B t, angle sum, 2 J1(x)/x series
+    "hollow_F": 93,      # 3 x (FP64 phase reduction, sincos, sin/x), 3 faces
+    "micelle_F": 96,     # core 3 j1(x)/x, sinc, two chain series, the sum
+    "cs_cyl_F": 80, "cs_ell_F": 52, "thick_box_F": 122,
+    "iso_orient": 0,
+    "ts_I": 8, "pcoil_I": 0, "mfrac_I": 60, "shell_F": 44, "ellcyl_F": 39,
+    "paracrystal_Z": 60,
+    "pev_I": 256,        # excluded-volume chain: two 32-node rules
+    "py_sq": 25,         # A10: series in x^2, 1/(1 + 24 phi G/x)
+    "sticky_sq": 50, "msf_I": 10, "sb_row": 22, "sb_node": 44, "lam_hg_F": 30, "caille_term": 24,
+    "neck_node": 44, "neck_unit": 12, "bhs_node": 20, "bhs_mat": 40, "rasp_F": 60, "belt_F": 80,
+    "ads_I": 8, "pr_node": 40, "attenuation": 1,
+    "weight": 3,         # A11
+    "detector": 0, "tally": 0,
 }
-_CLASSES = ("fp32", "int32", "mul64", "fp64", "trans32", "trans64")
-
-
-def step_slots(ops) -> float:
-    return sum(n * SLOT_COST[c] for n, c in zip(ops, _CLASSES))
-
-
 COMMON = ["source_slit", "slab", "scatter_point", "cone_q", "weight", "detector", "tally"]
 PATHS = {
     "tiny_sphere": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["sphere_F"],
@@ -183,27 +146,28 @@ PATHS = {
 #   hollow cylinder (size x mu nodes): Q_AB (sqrt), two 2 J1(x)/x series, the
 #   sinc series, the ring, F^2 and its weight: 52 ops + 1 trans32, 79 flops;
 #   per size node 4 ops.
-QUAD_NODE = {"quad_parallelepiped": ((15, 0, 0, 0, 0, 0), 24), "quad_spheroid": ((18, 0, 0, 0, 1, 0), 35),
-             "quad_capped_cylinder": STEP["cap_node"], "quad_hollow_prism": ((54, 12, 0, 0, 2, 0), 82),
-             "quad_hollow_cylinder": ((52, 0, 0, 0, 1, 0), 79)}
-QUAD_MU = {"quad_parallelepiped": ((12, 0, 0, 0, 0, 0), 20), "quad_spheroid": ((0, 0, 0, 0, 0, 0), 0),
-           "quad_capped_cylinder": ((57, 6, 0, 0, 1, 0), 83), "quad_hollow_prism": ((25, 6, 0, 0, 1, 0), 37),
-           "quad_hollow_cylinder": ((4, 0, 0, 0, 0, 0), 4)}
+QUAD_NODE = {"quad_parallelepiped": 24, "quad_spheroid": 35, "quad_capped_cylinder": STEP["cap_node"],
+             "quad_hollow_prism": 82, "quad_hollow_cylinder": 79}
+QUAD_MU = {"quad_parallelepiped": 20, "quad_spheroid": 0, "quad_capped_cylinder": 83,
+           "quad_hollow_prism": 37, "quad_hollow_cylinder": 4}
 QUAD_NODES = 76 * 76
-QUAD_BASE = COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["qvec"]
 
 
-def algo_per_neutron(workload: str):
-    """(FP32-FMA slots, FP32 flops) per neutron of a workload, or None."""
+def own_flops(workload: str):
+    """FP32 flops per neutron of a workload from the step counts, or None."""
     if workload in PATHS:
-        steps = PATHS[workload]
-        return (round(sum(step_slots(STEP[x][0]) for x in steps), 1), sum(STEP[x][1] for x in steps))
+        return sum(STEP[x] for x in PATHS[workload])
     if workload in QUAD_NODE:
-        base = sum(step_slots(STEP[x][0]) for x in QUAD_BASE)
-        (nops, nflops), (mops, mflops) = QUAD_NODE[workload], QUAD_MU[workload]
-        return (round(base + QUAD_NODES * step_slots(nops) + 76 * step_slots(mops), 1),
-                STEP["weight"][1] + QUAD_NODES * nflops + 76 * mflops)
+        return STEP["weight"] + QUAD_NODES * QUAD_NODE[workload] + 76 * QUAD_MU[workload]
     return None
+
+
+def algo_flops(workload: str):
+    """(FP32 flops per neutron, where the figure comes from) or None."""
+    if workload in REFERENCE_FLOPS:
+        return REFERENCE_FLOPS[workload], "per-neutron budget of the reference configurations"
+    f = own_flops(workload)
+    return None if f is None else (f, "step counts (series forms; lower bound)")
 
 
 def parse():
@@ -218,47 +182,66 @@ def parse():
                     help="time one trace call per neutron count 1e5 .. 1e10 instead")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample (0 = skip)")
+    ap.add_argument("--others", type=int, default=1,
+                    help="1: also time the other configurations (default workload only)")
     return ap.parse_args()
 
 
+def host_threads() -> int:
+    """Threads the CPU baseline uses: the cores this process may run on,
+    capped by OMP_NUM_THREADS where the host sets it (the GPU machine's CPU share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    if cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(params, seed, target_s):
+    """The FP64 oracle, compiled here for this host (-O3 -march=native), on
+    the first neutrons of the same workload: all allowed threads (about
+    target_s of work) and one thread (the paper's single-core scheme)."""
+    import tempfile
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
-    # calibrate the sample size on a probe long enough to hide thread start-up
-    n = 200_000
-    while True:
+    threads = host_threads()
+    with tempfile.TemporaryDirectory() as tmp:
+        so = oracle.build_native(tmp)
+        # calibrate the sample size on a probe long enough to hide thread start-up
+        n = 200_000
+        while True:
+            t0 = time.perf_counter()
+            oracle.trace_native(so, params, n, seed, nthreads=threads)
+            dt = time.perf_counter() - t0
+            if dt >= 0.5 or n >= 1 << 27:
+                break
+            n *= 4
+        rate = n / max(dt, 1e-9)
+        n_s = int(max(n, min(rate * target_s, 2e9)))
         t0 = time.perf_counter()
-        oracle.trace(params, n, seed, nthreads=threads)
+        oracle.trace_native(so, params, n_s, seed, nthreads=threads)
         dt = time.perf_counter() - t0
-        if dt >= 0.5 or n >= 1 << 27:
-            break
-        n *= 4
-    rate = n / max(dt, 1e-9)
-    n_s = int(max(n, min(rate * target_s, 2e9)))
-    t0 = time.perf_counter()
-    oracle.trace(params, n_s, seed, nthreads=threads)
-    dt = time.perf_counter() - t0
-    # one thread, the paper's single-core reference scheme (about 3 s of work)
-    n1 = int(max(20_000, min(rate / threads * 3.0, 5e8)))
-    t0 = time.perf_counter()
-    oracle.trace(params, n1, seed, nthreads=1)
-    dt1 = time.perf_counter() - t0
+        n1 = int(max(20_000, min(rate / threads * 3.0, 5e8)))
+        t0 = time.perf_counter()
+        oracle.trace_native(so, params, n1, seed, nthreads=1)
+        dt1 = time.perf_counter() - t0
     return dict(value=n_s / dt, unit="neutrons/s", cores=threads, kind="oracle",
                 sample=f"first {n_s} neutrons of the same workload and seed "
-                       f"(FP64 C oracle, {threads} threads, {dt:.1f} s)",
+                       f"(FP64 C oracle, gcc -O3 -march=native, {threads} threads, {dt:.1f} s)",
+                cpu=cpu_model(),
                 single_thread=dict(value=n1 / dt1, sample=f"first {n1} neutrons, 1 thread, {dt1:.1f} s"))
-
-
-def bench_valu_rates(a):
-    """Issue rates of the VALU operation classes the slot costs rest on."""
-    import torch
-    from paper_2501_06054_amd import sans
-    torch.cuda.set_device(0)
-    rates = sans.sans_debug_valu_rates()
-    return {"metric": "VALU issue rate", "unit": "wave64 instructions per clock per CU",
-            "rates": {k: round(v, 3) for k, v in rates.items()},
-            "slot_cost_vs_fp32_fma": {k: round(rates["fp32 fma"] / v, 2) for k, v in rates.items()},
-            "note": "the mul 32x32->64 class is a multiply plus an xor (two instructions)"}
 
 
 def bench_copy(a):
@@ -285,10 +268,11 @@ def bench_copy(a):
                                             "bytes_written": nbytes // 2}}
 
 
-def bench_batch(a):
-    """The batched high-throughput set: 4096 experiments, one persistent
-    graph-captured launch per step; compared with plain per-experiment
-    traces of a subset on the same GPU."""
+def batch_rates(steps: int, warmup: int):
+    """The 4096-experiment set in one persistent graph-captured launch per
+    step, against plain per-experiment traces of its first 256 experiments on
+    the same GPU."""
+    import tempfile
     import torch
     from paper_2501_06054_amd import sans, workloads as W
 
@@ -300,19 +284,20 @@ def bench_batch(a):
     torch.cuda.set_device(0)
     out = torch.empty((len(exps), 128, 128), dtype=torch.float64, device="cuda")
     # the autotuner's cache (one entry per batch shape) lives outside the tree
-    import tempfile
     tune = os.path.join(tempfile.gettempdir(), "sans_batch_tuning.json")
+    t0 = time.perf_counter()
     sans.sans_trace_batch(plist, ns, seeds, out, tune_cache=tune)   # tunes once (cached file)
-    for _ in range(a.warmup):
+    torch.cuda.synchronize()
+    first_s = time.perf_counter() - t0
+    for _ in range(warmup):
         sans.sans_trace_batch(plist, ns, seeds, out, tune_cache=tune)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for _ in range(steps):
         sans.sans_trace_batch(plist, ns, seeds, out, tune_cache=tune)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    value = total * a.steps / elapsed
-    # plain path on the first 256 experiments (model set-up outside the timing)
+    value = total * steps / elapsed
     sub = range(256)
     models = [sans.Model(exps[e]["params"]) for e in sub]
     dets = [m.detector() for m in models]
@@ -324,20 +309,29 @@ def bench_batch(a):
     plain_rate = sum(ns[e] for e in sub) / (time.perf_counter() - t0)
     for m in models:
         m.close()
+    return dict(experiments=len(exps), total_neutrons=total, ms_per_call=round(elapsed / steps * 1e3, 3),
+                value=round(value, 1), unit="neutrons/s", first_call_s=round(first_s, 3),
+                plain_same_gpu=dict(value=round(plain_rate, 1), unit="neutrons/s",
+                                    sample="first 256 experiments, one sans_trace_ex each"),
+                batched_over_plain=round(value / plain_rate, 3))
+
+
+def bench_batch(a):
+    """The batched set as the bench line (--workload batch)."""
+    r = batch_rates(a.steps, a.warmup)
     return {
         "metric": "neutrons traced/s at 1 GPU",
-        "value": round(value, 1),
+        "value": r["value"],
         "unit": "neutrons/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": round(elapsed / a.steps * 1e3, 3),
+        "ms_per_step": r["ms_per_call"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 weights, f64 geometry and tallies",
         "data": "synthetic (seeded experiment generator, Philox streams)",
-        "config": {"workload": "batch", "experiments": len(exps), "total_neutrons": total,
+        "config": {"workload": "batch", "experiments": r["experiments"], "total_neutrons": r["total_neutrons"],
                    "detector": "128x128 each", "parallelism": "none (1 GPU)"},
-        "plain_same_gpu": {"value": round(plain_rate, 1), "unit": "neutrons/s",
-                           "sample": "first 256 experiments, one sans_trace_ex each"},
-        "batched_over_plain": round(value / plain_rate, 3),
+        "plain_same_gpu": r["plain_same_gpu"],
+        "batched_over_plain": r["batched_over_plain"],
     }
 
 
@@ -396,6 +390,102 @@ def measured_traffic(workload: str, kernel: str, n: int):
     return None
 
 
+def roofline_of(workload: str, n: int, call_ms: float):
+    """The trace call against the FP32 vector peak (the call's kernels timed
+    together with HIP events on their stream)."""
+    algo = algo_flops(workload)
+    if algo is None:
+        return None
+    flops, source = algo
+    ach = flops * n / (call_ms * 1e-3) / 1e12
+    traffic = measured_traffic(workload, "trace_call", n)
+    return dict(bound="alu", achieved=round(ach, 4), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                frac=round(ach / PEAK_FP32_TFLOPS, 5),
+                traffic=(None if traffic is None else round(traffic[0] + traffic[1])),
+                flops_per_neutron=flops, flops_source=source, own_count=own_flops(workload),
+                timed="one sans_trace call: all of its kernels (trace launches and tally "
+                      "reduction), HIP events on its stream",
+                call_ms=round(call_ms, 4), neutrons_per_call=n)
+
+
+def measured_valu(workload: str):
+    """Counter-measured VALU work of the workload's trace kernel from the
+    committed summary (profiles/valu_counters.md), or None when it was taken
+    on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "valu_counters.md")
+    if not os.path.exists(path):
+        return None
+    src = kernel_source_hash()
+    keys = ("kernel", "valu_instr_per_neutron", "fp32_flops_per_neutron", "fp64_instr_per_neutron",
+            "valu_busy", "clock_mhz")
+    for line in open(path):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 8 and cells[0] == workload and cells[2] == src:
+            try:
+                vals = [cells[1]] + [float(c) for c in cells[3:]]
+            except ValueError:
+                return None
+            return dict(zip(keys, vals), source="rocprofv3 counters, profiles/valu_counters.md")
+    return None
+
+
+def time_calls(m, n, seed, steps, warm_n=None):
+    """Mean time (ms) of `steps` trace calls of n neutrons on a warm model,
+    HIP events on the stream its kernels run on; the detector."""
+    import torch
+    stream = torch.cuda.current_stream()
+    det = m.detector()
+    m.trace(warm_n or n, seed, det=det)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(stream)
+        m.trace(n, seed, det=det)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return sum(e0.elapsed_time(e1) for e0, e1 in ev) / steps, det
+
+
+def other_configs():
+    """The other configurations on the same GPU: oriented cylinder and
+    ellipsoid (1e9 neutrons each), the 4096-experiment batch against plain
+    per-experiment traces, and each surrogate against the exact-average trace
+    of the same workload."""
+    import torch
+    from paper_2501_06054_amd import sans, surrogate as SG, workloads as W
+    out = {}
+    for name in ("oriented_cylinder", "oriented_ellipsoid"):
+        wl = W.workload(name)
+        m = sans.Model(wl["params"])
+        ms, _ = time_calls(m, int(wl["n"]), wl["seed"], 3)
+        m.close()
+        n = int(wl["n"])
+        out[name] = dict(neutrons_per_call=n, ms_per_call=round(ms, 3), value=round(n / (ms * 1e-3), 1),
+                         unit="neutrons/s", roofline=roofline_of(name, n, ms))
+    b = batch_rates(steps=2, warmup=1)
+    out["batch"] = b
+    for model in ("parallelepiped", "spheroid"):
+        sw, qw = W.workload(f"surrogate_{model}"), W.workload(f"quad_{model}")
+        ms_ = sans.Model(sw["params"])
+        SG.Surrogate.load(model).attach(ms_.handle)
+        n_s = 10 ** 9
+        t_s, _ = time_calls(ms_, n_s, sw["seed"], 1, warm_n=10 ** 8)
+        ms_.close()
+        mq = sans.Model(qw["params"])
+        n_q = 10 ** 8
+        t_q, _ = time_calls(mq, n_q, qw["seed"], 1, warm_n=10 ** 7)
+        mq.close()
+        r_s, r_q = n_s / (t_s * 1e-3), n_q / (t_q * 1e-3)
+        out[f"surrogate_{model}"] = dict(neutrons_per_call=n_s, ms_per_call=round(t_s, 3), value=round(r_s, 1),
+                                         unit="neutrons/s",
+                                         exact_average=dict(workload=f"quad_{model}", neutrons_per_call=n_q,
+                                                            value=round(r_q, 1),
+                                                            roofline=roofline_of(f"quad_{model}", n_q, t_q)),
+                                         surrogate_over_exact=round(r_s / r_q, 3))
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -409,9 +499,6 @@ def main():
         return
     if a.workload == "copy":
         print(json.dumps(bench_copy(a)), flush=True)
-        return
-    if a.workload == "valu_rates":
-        print(json.dumps(bench_valu_rates(a)), flush=True)
         return
 
     import torch
@@ -463,23 +550,7 @@ def main():
     value = n * a.steps / elapsed
     kernel_rate = n / (kernel_ms * 1e-3)
 
-    algo = algo_per_neutron(a.workload)
-    roofline = fp32 = None
-    if algo:
-        slots, flops = algo
-        ach = slots * kernel_rate / 1e12
-        traffic = measured_traffic(a.workload, "trace_call", n)
-        roofline = dict(bound="alu", achieved=round(ach, 3), peak=round(PEAK_VALU_TSLOTS, 3),
-                        unit="T FP32-FMA lane slots/s (VALU issue, 157.3 TFLOP/s / 2)",
-                        frac=round(ach / PEAK_VALU_TSLOTS, 4),
-                        traffic=(None if traffic is None else round(traffic[0] + traffic[1])),
-                        timed="one sans_trace call: all of its kernels (trace kernel launches and "
-                              "tally reduction), HIP events on its stream",
-                        call_ms=round(kernel_ms, 4), slots_per_neutron=slots, neutrons_per_call=n)
-        fach = flops * kernel_rate / 1e12
-        fp32 = dict(achieved=round(fach, 4), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                    frac=round(fach / PEAK_FP32_TFLOPS, 5), flops_per_neutron=flops)
-
+    roofline = roofline_of(a.workload, n, kernel_ms)
     out = {
         "metric": "neutrons traced/s at 1 GPU",
         "value": round(value, 1),
@@ -499,11 +570,13 @@ def main():
         "detector_total": total,
         "setup_ms": round(setup_ms, 3),
         "roofline": roofline,
-        "fp32_valu": fp32,
+        "valu": measured_valu(a.workload),
     }
+    m.close()
+    if a.others and a.workload == "coreshell_py" and not a.n:
+        out["other_configs"] = other_configs()
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(p, seed, a.cpu_seconds)
-    m.close()
     print(json.dumps(out), flush=True)
 
 

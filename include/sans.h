@@ -455,15 +455,6 @@ int sans_trace_noalloc(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed
 int sans_debug_trace(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed,
                      uint32_t exp_id, int32_t* pixel, float* w, float* q, void* stream);
 
-/* Measured VALU issue rates (synchronous; about 10 ms): rates (host double
- * [6]) receives wave64 instructions per clock per compute unit, at the
- * device's nominal clock, of dependency-free streams of (0) 32-bit integer
- * xor/add, (1) a 32x32->64 multiply followed by an xor (two instructions),
- * (2) FP32 FMA, (3) FP64 FMA, (4) FP32 reciprocal, (5) FP64 reciprocal.
- * They weigh the algorithmic operation counts of the throughput report
- * (one FP32 FMA per lane per clock per SIMD of 16 lanes = 1.0). */
-int sans_debug_valu_rates(double* rates, void* stream);
-
 /* Raw Philox4x32-10 words (Salmon et al., SC'11) of the neutron streams:
  * out (device uint32 [n][n_blocks][4]) receives block b of neutron first+j,
  * counter (lo i, hi i, b, exp_id), key (lo seed, hi seed). */

@@ -5,6 +5,8 @@ CPU-baseline leg of the benchmark.  The product package never imports it.
 
 ``build()`` compiles ``liboracle.so`` with gcc (plain C99 + pthreads,
 ``-O2 -ffp-contract=off``); ``lib()`` loads it, building it when missing.
+``build_native()`` compiles a copy for the host it runs on (``-O3
+-march=native``), which the benchmark's CPU baseline times.
 """
 from __future__ import annotations
 
@@ -60,13 +62,48 @@ class OrcParams(C.Structure):
     ]
 
 
+def _compile(out: str, opt) -> None:
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", *opt, "-std=c99", "-D_GNU_SOURCE", "-ffp-contract=off",
+                           "-fPIC", "-shared", "-o", tmp, SRC, "-lm", "-lpthread"])
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
     if force or not os.path.exists(SO) or os.path.getmtime(SO) < os.path.getmtime(SRC):
-        tmp = SO + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-ffp-contract=off",
-                               "-fPIC", "-shared", "-o", tmp, SRC, "-lm", "-lpthread"])
-        os.replace(tmp, SO)
+        _compile(SO, ["-O2"])
     return SO
+
+
+def build_native(out_dir: str) -> str:
+    """A copy of the oracle compiled for the CPU it runs on (-O3
+    -march=native, still without FMA contraction), for timing it on that
+    host; built on the spot, never shipped to another machine."""
+    so = os.path.join(out_dir, "liboracle_native.so")
+    _compile(so, ["-O3", "-march=native"])
+    return so
+
+
+_NATIVE = {}
+
+
+def trace_native(so_path: str, p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0,
+                 nthreads: int = 1) -> np.ndarray:
+    """trace() through the library at so_path (a build_native() copy)."""
+    L = _NATIVE.get(so_path)
+    if L is None:
+        L = C.CDLL(so_path)
+        P = C.POINTER
+        L.orc_trace.argtypes = [P(OrcParams), C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, C.c_int32,
+                                P(C.c_double), P(C.c_double), P(C.c_uint64)]
+        L.orc_trace.restype = C.c_int32
+        _NATIVE[so_path] = L
+    o = to_params(p)
+    det = np.zeros((p["ny"], p["nx"]))
+    rc = L.orc_trace(C.byref(o), first, n, seed, exp_id, nthreads, _ptr(det, C.c_double), None, None)
+    if rc != 0:
+        raise ValueError(f"oracle trace failed ({rc})")
+    return det
 
 
 _LIB = None

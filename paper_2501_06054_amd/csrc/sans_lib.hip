@@ -269,44 +269,6 @@ __global__ __launch_bounds__(kSchulzBlock) void k_schulz_tables(const SchulzJob*
     }
 }
 
-// ------------------------------------------------------------------ VALU issue-rate probe
-// Eight independent dependency chains per lane of one operation class; the
-// issue cost of each class (relative to an FP32 FMA) weighs the algorithmic
-// operation counts of the trace kernels.
-constexpr int kProbeIter = 2048;
-constexpr int kProbeChains = 8;
-
-template <int OP>
-__global__ __launch_bounds__(256) void k_valu_probe(uint32_t* out, uint32_t seed)
-{
-    uint32_t u[kProbeChains];
-    double d[kProbeChains];
-    float f[kProbeChains];
-#pragma unroll
-    for (int j = 0; j < kProbeChains; ++j) {
-        u[j] = threadIdx.x * 2654435761u + (uint32_t)j * 77u + seed;
-        d[j] = 1.0 + 1e-3 * (double)threadIdx.x + j;
-        f[j] = 1.0f + 1e-3f * (float)threadIdx.x + (float)j;
-    }
-    for (int i = 0; i < kProbeIter; ++i) {
-#pragma unroll
-        for (int j = 0; j < kProbeChains; ++j) {
-            if constexpr (OP == 0) u[j] = (u[j] ^ (seed + (uint32_t)j)) + 0x9E3779B9u;        // 2 int32 ops
-            if constexpr (OP == 1) {                                                          // mul64 + xor
-                const uint64_t p = (uint64_t)0xD2511F53u * u[j];
-                u[j] = (uint32_t)p ^ (uint32_t)(p >> 32);
-            }
-            if constexpr (OP == 2) f[j] = __builtin_fmaf(f[j], 0.999f, 0.25f);
-            if constexpr (OP == 3) d[j] = __builtin_fma(d[j], 0.999, 0.25);
-            if constexpr (OP == 4) f[j] = __builtin_amdgcn_rcpf(f[j]);
-            if constexpr (OP == 5) d[j] = __builtin_amdgcn_rcp(d[j]);
-        }
-    }
-    uint32_t r = 0;
-#pragma unroll
-    for (int j = 0; j < kProbeChains; ++j) r ^= u[j] ^ __float_as_uint(f[j]) ^ (uint32_t)__double_as_longlong(d[j]);
-    out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = r;
-}
 
 // ------------------------------------------------------------------ dispatch table
 // Kernel pointers of every model, filled once by the kind-group translation
@@ -1781,45 +1743,6 @@ int sans_debug_philox(uint64_t seed, uint64_t first, uint64_t n, uint32_t n_bloc
     hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
                        (uint32_t)seed, (uint32_t)(seed >> 32), first, n, n_blocks, exp_id, out);
     HIP_TRY(hipGetLastError());
-    return SANS_OK;
-}
-
-int sans_debug_valu_rates(double* rates, void* stream)
-{
-    (void)hipGetLastError();  // a stale error of an earlier call is not ours
-    if (!rates) return fail(SANS_E_INVALID_ARG, "rates is NULL");
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    HIP_TRY(hipGetDeviceProperties(&prop, dev));
-    const unsigned blocks = (unsigned)prop.multiProcessorCount * 16, threads = 256;
-    hipStream_t s = (hipStream_t)stream;
-    uint32_t* out = nullptr;
-    HIP_TRY(hipMalloc(&out, sizeof(uint32_t) * blocks * threads));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    using Probe = void (*)(uint32_t*, uint32_t);
-    const Probe probes[6] = {k_valu_probe<0>, k_valu_probe<1>, k_valu_probe<2>,
-                             k_valu_probe<3>, k_valu_probe<4>, k_valu_probe<5>};
-    const int per_step[6] = {2, 2, 1, 1, 1, 1};
-    for (int k = 0; k < 6 && e == hipSuccess; ++k) {
-        hipLaunchKernelGGL(probes[k], dim3(blocks), dim3(threads), 0, s, out, 3u);   // warm
-        (void)hipEventRecord(e0, s);
-        hipLaunchKernelGGL(probes[k], dim3(blocks), dim3(threads), 0, s, out, 5u);
-        (void)hipEventRecord(e1, s);
-        e = hipGetLastError();
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        const double waves = (double)blocks * threads / 64.0;
-        const double instr = waves * kProbeIter * kProbeChains * per_step[k];
-        rates[k] = instr / (ms * 1e-3) / (prop.clockRate * 1e3) / prop.multiProcessorCount;
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(out);
-    if (e != hipSuccess) return fail(SANS_E_HIP, std::string("valu probe: ") + hipGetErrorString(e));
     return SANS_OK;
 }
 

@@ -95,8 +95,6 @@ def _load():
     L.sans_batch_release.argtypes = []
     L.sans_model_attach_surrogate.argtypes = [vp, vp, P(C.c_float), P(C.c_float)]
     L.sans_model_attach_surrogate.restype = C.c_int
-    L.sans_debug_valu_rates.argtypes = [P(C.c_double), vp]
-    L.sans_debug_valu_rates.restype = C.c_int
     L.sans_pq_dataset.argtypes = [i32, vp, i64, vp, i32, vp]
     L.sans_pq_dataset.restype = C.c_int
     L.sans_mlp_param_count.restype = i64
@@ -321,16 +319,6 @@ def sans_mse_grad(y, t, dy, loss=None, stream=None) -> None:
 def sans_f32_to_bf16(x, y, stream=None) -> None:
     _mcheck(lib.sans_f32_to_bf16(_dev(x, torch.float32, "x"), _dev(y, torch.bfloat16, "y"), x.numel(),
                                  _stream(stream)), "sans_f32_to_bf16")
-
-
-VALU_RATE_NAMES = ("int32 xor/add", "mul 32x32->64 + xor", "fp32 fma", "fp64 fma", "fp32 rcp", "fp64 rcp")
-
-
-def sans_debug_valu_rates(stream=None) -> dict:
-    """Measured wave64 VALU instructions per clock per CU, by class."""
-    out = (C.c_double * 6)()
-    _check(lib.sans_debug_valu_rates(out, _stream(stream)), "sans_debug_valu_rates")
-    return dict(zip(VALU_RATE_NAMES, [float(v) for v in out]))
 
 
 def sans_pq_dataset(kind: str, x, out, quad_n: int = 76, stream=None) -> None:

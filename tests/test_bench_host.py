@@ -1,5 +1,7 @@
-"""Host logic of bench.py (CPU): the per-neutron slot model, the lookup of
-counter-measured HBM traffic, and the one-GPU guard.  No GPU is touched."""
+"""Host logic of bench.py (CPU): the per-neutron FP32 flop counts behind the
+roofline, the lookup of counter-measured HBM traffic and VALU work, the host
+thread count of the CPU baseline, and the one-GPU guard.  No GPU is
+touched."""
 import os
 import subprocess
 import sys
@@ -13,20 +15,33 @@ import bench  # noqa: E402
 from paper_2501_06054_amd import workloads as W  # noqa: E402
 
 
-def test_every_workload_has_a_work_count():
-    """Each Monte Carlo or quadrature workload carries an algorithmic count
-    (the roofline's numerator); the surrogate ones are timed against MFMA."""
+def test_every_workload_has_a_flop_count():
+    """Each Monte Carlo or quadrature workload carries an algorithmic FP32
+    count (the roofline's numerator); the surrogate ones are timed against
+    the exact-average trace instead."""
     for name in W.WORKLOADS:
         mode = W.workload(name)["params"]["mode"]
-        algo = bench.algo_per_neutron(name)
+        algo = bench.algo_flops(name)
         if mode == "surrogate":
             assert algo is None, name
             continue
         assert algo is not None, name
-        slots, flops = algo
-        assert slots > 0 and flops >= 0, name
+        flops, source = algo
+        assert flops > 0 and source, name
         if mode == "quad":
             assert name in bench.QUAD_NODE and name in bench.QUAD_MU, name
+
+
+def test_reference_configurations_take_the_reference_budget():
+    # the four reference configurations
+    assert bench.algo_flops("coreshell_py")[0] == 110
+    assert bench.algo_flops("tiny_sphere")[0] == 35
+    assert bench.algo_flops("oriented_cylinder")[0] == 80
+    assert bench.algo_flops("oriented_ellipsoid")[0] == 80
+    assert bench.algo_flops("quad_parallelepiped")[0] == bench.own_flops("quad_parallelepiped")
+    # the step counts stay a lower bound of them (series forms)
+    for name in bench.REFERENCE_FLOPS:
+        assert bench.own_flops(name) <= bench.REFERENCE_FLOPS[name], name
 
 
 def test_paths_name_only_counted_steps():
@@ -38,30 +53,50 @@ def test_paths_name_only_counted_steps():
             assert s in steps, (name, s)
 
 
-@pytest.mark.parametrize("cls", bench._CLASSES)
-def test_step_slots_is_linear_in_the_class_costs(cls):
-    unit = tuple(1 if c == cls else 0 for c in bench._CLASSES)
-    assert bench.step_slots(unit) == pytest.approx(bench.SLOT_COST[cls])
-    assert bench.step_slots(tuple(3 * u for u in unit)) == pytest.approx(3 * bench.SLOT_COST[cls])
-    assert bench.step_slots((0,) * len(bench._CLASSES)) == 0.0
-
-
 def test_quadrature_count_scales_with_its_nodes():
-    """The quadrature workloads' count is the Monte Carlo base plus the
-    per-node and per-mu-node costs times 76 x 76 and 76 nodes."""
-    base = sum(bench.step_slots(bench.STEP[x][0]) for x in bench.QUAD_BASE)
+    """The quadrature workloads' count is the weight plus the per-node and
+    per-mu-node flops times 76 x 76 and 76 nodes."""
     for name in bench.QUAD_NODE:
-        slots, _ = bench.algo_per_neutron(name)
-        node = bench.step_slots(bench.QUAD_NODE[name][0])
-        mu = bench.step_slots(bench.QUAD_MU[name][0])
-        assert slots == pytest.approx(base + bench.QUAD_NODES * node + 76 * mu, abs=0.1)
-        assert slots > bench.QUAD_NODES * node
+        flops = bench.own_flops(name)
+        assert flops == bench.STEP["weight"] + bench.QUAD_NODES * bench.QUAD_NODE[name] + 76 * bench.QUAD_MU[name]
 
 
 def test_peak_follows_the_unit_counts():
     # 256 CUs x 2.4 GHz x 128 FP32 FMA lanes per clock x 2 flops
     assert bench.CUS * bench.CLOCK_GHZ * 128 * 2 / 1e3 == pytest.approx(bench.PEAK_FP32_TFLOPS, rel=2e-3)
-    assert bench.PEAK_VALU_TSLOTS == pytest.approx(bench.PEAK_FP32_TFLOPS / 2)
+
+
+def test_roofline_is_the_fp32_fraction(monkeypatch):
+    monkeypatch.setattr(bench, "measured_traffic", lambda *a: None)
+    r = bench.roofline_of("coreshell_py", 10**8, 2.0)
+    # 110 flops x 1e8 neutrons in 2 ms = 5.5 TFLOP/s
+    assert r["achieved"] == pytest.approx(5.5)
+    assert r["peak"] == bench.PEAK_FP32_TFLOPS and r["unit"] == "TFLOP/s"
+    assert r["frac"] == pytest.approx(5.5 / 157.3, abs=1e-5)
+    assert bench.roofline_of("surrogate_parallelepiped", 10, 1.0) is None
+
+
+def test_host_threads_respects_the_cpu_share(monkeypatch):
+    monkeypatch.setenv("OMP_NUM_THREADS", "3")
+    assert bench.host_threads() == min(3, len(os.sched_getaffinity(0)))
+    monkeypatch.setenv("OMP_NUM_THREADS", "")
+    assert bench.host_threads() == len(os.sched_getaffinity(0))
+    assert bench.cpu_model()
+
+
+def test_measured_valu_needs_matching_sources(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "valu_counters.md").write_text(
+        "| workload | kernel | sources | VALU/neutron | FP32 flops/neutron | FP64/neutron | busy | MHz |\n"
+        "|---|---|---|---|---|---|---|---|\n"
+        "| wl_a | k_emit<1, 0> | 0123456789abcdef | 11.5 | 201 | 2.2 | 0.93 | 2100 |\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0123456789abcdef")
+    v = bench.measured_valu("wl_a")
+    assert v["kernel"] == "k_emit<1, 0>" and v["valu_instr_per_neutron"] == 11.5 and v["clock_mhz"] == 2100
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "fedcba9876543210")
+    assert bench.measured_valu("wl_a") is None
 
 
 def test_measured_traffic_needs_matching_sources(tmp_path, monkeypatch):
