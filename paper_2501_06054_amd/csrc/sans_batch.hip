@@ -20,13 +20,13 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         if (ti >= ntiles) break;
         const BatchTile tl = tiles[ti];
         const unsigned e = __builtin_amdgcn_readfirstlane(tl.e);
-        const TraceArgs& a = exps[e];
+        ConstArgs* a = (ConstArgs*)(exps + e);
         for (int i = threadIdx.x; i < npix; i += blockDim.x) hist[i] = 0.0;
         // the Schulz table stays in global memory (L2/L1): the histogram
         // takes the workgroup's LDS
-        const double* tab = a.tab_size;
+        const double* tab = a->tab_size;
         __syncthreads();
-        switch (a.kind) {
+        switch (a->kind) {
         case 0: batch_tile<0>(a, tl.first, tl.count, hist, tab); break;
         case 1: batch_tile<1>(a, tl.first, tl.count, hist, tab); break;
         case 2: batch_tile<2>(a, tl.first, tl.count, hist, tab); break;

@@ -169,6 +169,14 @@ struct U4 {
 __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                             uint32_t k0, uint32_t k1)
 {
+    // The key is uniform across the wave (one seed per launch or per batch
+    // tile), so it can live in scalar registers.  Its value is hidden here
+    // so that the nine round-key
+    // increments are recomputed with scalar adds at every call instead of
+    // being hoisted out of the neutron loop, where twenty loop-invariant
+    // round keys overflow the scalar registers and come back through VALU
+    // lane reads.
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         // one 32x32->64 multiply per word (v_mad_u64_u32 gives both halves)

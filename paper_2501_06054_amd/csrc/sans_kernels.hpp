@@ -6,7 +6,7 @@
 //   k_emit<KIND, MODE>          the hot path for larger detectors: events binned
 //                               by detector row band (summed by k_bin_accumulate)
 //   k_trace<KIND, MODE, TALLY>  atomic tallies (global / per-XCD replica)
-//   k_debug<KIND, MODE>         the same per-neutron code, writing (pixel, w, q)
+//   k_debug<KIND, MODE, ATT>    the same per-neutron code, writing (pixel, w, q)
 //   k_pq_avg<KIND>              the exact average <F^2>(q) alone
 //   k_trace_sur<KIND>,          surrogate mode: the network inside the tracer and
 //   k_trace_queue<KIND>         the exact pass over the queued neutrons
@@ -63,6 +63,28 @@ __device__ __forceinline__ LdsPtrs stage_all(const TraceArgs& a, const LdsLayout
     return p;
 }
 
+// The trace constants as seen from inside a neutron loop.  They sit in
+// memory that no kernel writes (the kernel's argument segment, or the batch's
+// parameter array) and are read through a pointer whose value is hidden from
+// the compiler at every neutron, so their scalar loads stay inside the loop
+// as scalar-cache hits.  Loop-invariant loads hoisted out of the loop would
+// overflow the scalar registers (a TraceArgs is a hundred doubles) and come
+// back through VALU lane reads, one issue slot each.
+using ConstArgs = const __attribute__((address_space(4))) TraceArgs;
+
+__device__ __forceinline__ const TraceArgs& loop_args(ConstArgs* p)
+{
+    asm volatile("" : "+s"(p));
+    return *(const TraceArgs*)p;
+}
+
+// The trace kernels take their TraceArgs as the first argument, which the
+// argument segment holds at offset 0.
+__device__ __forceinline__ ConstArgs* kernel_args()
+{
+    return (ConstArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
 // Atomic tallies: one FP64 atomic per detected neutron into the detector
 // (GLOBAL) or into this XCD's replica of it (XCD).
 template <int KIND, int MODE, int TALLY>
@@ -80,7 +102,8 @@ __global__ __launch_bounds__(kBlock) void k_trace(const TraceArgs a, LdsLayout l
     }
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += stride) {
-        const Event ev = trace_neutron<KIND, MODE, true>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
+        const Event ev = trace_neutron<KIND, MODE, true>(loop_args(kernel_args()), a.first + j, lp.tsize,
+                                                         lp.tnorm, lp.lq);
         if (ev.pixel >= 0) {
             const double w = (double)ev.w;
             __hip_atomic_fetch_add(target + ev.pixel, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -110,7 +133,8 @@ __global__ __launch_bounds__(kHistBlock) void k_trace_hist(const TraceArgs a, Ld
     __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += stride) {
-        const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
+        const Event ev = trace_neutron<KIND, MODE>(loop_args(kernel_args()), a.first + j, lp.tsize, lp.tnorm,
+                                                   lp.lq);
         if (ev.pixel >= 0)
             __hip_atomic_fetch_add(lp.hist + ev.pixel, (double)ev.w, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -147,7 +171,8 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const TraceArgs a, LdsLayou
         unsigned local = 0;
         float w = 0.0f;
         if (j < a.n) {
-            const Event ev = trace_neutron<KIND, MODE>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
+            const Event ev = trace_neutron<KIND, MODE>(loop_args(kernel_args()), a.first + j, lp.tsize,
+                                                       lp.tnorm, lp.lq);
             if (ev.pixel >= 0) {
                 t = ev.pixel / tile_pixels;
                 local = (unsigned)(ev.pixel - t * tile_pixels);
@@ -173,7 +198,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const TraceArgs a, LdsLayou
     if (lane < ntiles) seg_count[(size_t)lane * nwaves + wv] = count;
 }
 
-template <int KIND, int MODE>
+template <int KIND, int MODE, bool ATT>
 __global__ __launch_bounds__(kBlock) void k_debug(const TraceArgs a, LdsLayout lay, int32_t* pixel,
                                                   float* w, float* q)
 {
@@ -182,7 +207,8 @@ __global__ __launch_bounds__(kBlock) void k_debug(const TraceArgs a, LdsLayout l
     __syncthreads();
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.n) return;
-    const Event ev = trace_neutron<KIND, MODE, true>(a, a.first + j, lp.tsize, lp.tnorm, lp.lq);
+    const Event ev = trace_neutron<KIND, MODE, ATT>(loop_args(kernel_args()), a.first + j, lp.tsize, lp.tnorm,
+                                                    lp.lq);
     if (pixel) pixel[j] = ev.pixel;
     if (w) w[j] = ev.w;
     if (q) q[j] = ev.q;
@@ -220,10 +246,11 @@ struct BatchTile {
 };
 
 template <int KIND>
-__device__ __forceinline__ void batch_tile(const TraceArgs& a, unsigned long long first, unsigned count,
+__device__ __forceinline__ void batch_tile(ConstArgs* ap, unsigned long long first, unsigned count,
                                            double* hist, const double* tab)
 {
     for (unsigned j = threadIdx.x; j < count; j += blockDim.x) {
+        const TraceArgs& a = loop_args(ap);
         const Event ev = trace_neutron<KIND, 0>(a, first + j, tab, a.tab_norm, nullptr);
         if (ev.pixel >= 0)
             __hip_atomic_fetch_add(hist + ev.pixel, (double)ev.w, __ATOMIC_RELAXED,
@@ -264,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const m
         const uint64_t j = j0 + threadIdx.x;
         const bool valid = j < a.n;
         Event ev{-1, 0.0f, 0.0f};
-        if (valid) ev = trace_neutron<KIND, 2>(a, a.first + j, nullptr, nullptr, nullptr);
+        if (valid) ev = trace_neutron<KIND, 2>(loop_args(kernel_args()), a.first + j, nullptr, nullptr, nullptr);
         const float x0 = __logf(ev.q) + sc.ls0;
         const bool in_dom = valid && ev.pixel >= 0 && x0 >= sc.lo0 && x0 <= sc.hi0;
         float* xr = xs + lane * mlp::kIn;
@@ -312,7 +339,8 @@ __global__ __launch_bounds__(kBlock) void k_trace_queue(const TraceArgs a, LdsLa
     const int lane = threadIdx.x & 63;
     const unsigned waves = gridDim.x * (blockDim.x / 64);
     for (unsigned i = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); i < nq; i += waves) {
-        const Event ev = trace_neutron<KIND, 1>(a, queue[i], lp.tsize, lp.tnorm, lp.lq, lane, 64);
+        const Event ev = trace_neutron<KIND, 1>(loop_args(kernel_args()), queue[i], lp.tsize, lp.tnorm, lp.lq,
+                                                lane, 64);
         float w = ev.w;
         for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
         if (lane == 0 && ev.pixel >= 0)
@@ -404,12 +432,14 @@ using DebugFn = void (*)(const TraceArgs, LdsLayout, int32_t*, float*, float*);
 using PqFn = void (*)(const TraceArgs, LdsLayout, const float*, const float*, int64_t, float*);
 
 // The kernels of one model: [mode] for MC (0) and QUAD (1); trace[mode][0]
-// tallies with global atomics, trace[mode][1] into per-XCD replicas.
+// tallies with global atomics, trace[mode][1] into per-XCD replicas.  The
+// atomic kernels carry the attenuation; the histogram and binned kernels
+// (unattenuated Monte Carlo runs) do not.
 struct KindFns {
     TraceFn trace[2][2];
     HistFn hist[2];
     EmitFn emit[2];
-    DebugFn debug[2];
+    DebugFn debug[2][2];   // [mode][attenuation compiled in]
     PqFn pq;
 };
 
@@ -425,8 +455,12 @@ void fill_kind(KindFns* t)
     f.hist[1] = k_trace_hist<K, 1>;
     f.emit[0] = k_emit<K, 0>;
     f.emit[1] = k_emit<K, 1>;
-    f.debug[0] = k_debug<K, 0>;
-    f.debug[1] = k_debug<K, 1>;
+    // the per-neutron kernel compiles the same instance of the neutron code as
+    // the kernels that tally: the attenuation only where those carry it
+    f.debug[0][0] = k_debug<K, 0, false>;
+    f.debug[0][1] = k_debug<K, 0, true>;
+    f.debug[1][0] = k_debug<K, 1, true>;
+    f.debug[1][1] = k_debug<K, 1, true>;
     f.pq = k_pq_avg<K>;
 }
 

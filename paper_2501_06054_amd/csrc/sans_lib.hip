@@ -309,9 +309,9 @@ EmitFn pick_emit(int kind, int mode)
     return known_kind(kind) ? kind_table()[kind].emit[mode == 0 ? 0 : 1] : nullptr;
 }
 
-DebugFn pick_debug(int kind, int mode)
+DebugFn pick_debug(int kind, int mode, bool att)
 {
-    return known_kind(kind) ? kind_table()[kind].debug[mode == 0 ? 0 : 1] : nullptr;
+    return known_kind(kind) ? kind_table()[kind].debug[mode == 0 ? 0 : 1][att ? 1 : 0] : nullptr;
 }
 
 PqFn pick_pq(int kind) { return known_kind(kind) ? kind_table()[kind].pq : nullptr; }
@@ -1724,7 +1724,7 @@ int sans_debug_trace(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, 
     a.seed_hi = (uint32_t)(seed >> 32);
     a.exp_id = exp_id;
     const LdsLayout lay = layout(m, false);
-    DebugFn fn = pick_debug(m->p.kind, m->p.mode);
+    DebugFn fn = pick_debug(m->p.kind, m->p.mode, m->p.mu_att > 0.0);
     if (!fn) return fail(SANS_E_UNSUPPORTED, "no kernel for this model");
     hipLaunchKernelGGL(fn, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), lds_bytes(lay),
                        (hipStream_t)stream, a, lay, pixel, w, q);
