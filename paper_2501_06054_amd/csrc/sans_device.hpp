@@ -81,6 +81,18 @@ struct TraceArgs {
     double inv_px, inv_py;        // nx / det_w, ny / det_h
     double wscale;                // 1e10 * dOmega * phi / <V>  (per metre of path)
     int32_t nx, ny;
+    // FP32 geometry of isotropic models (fast_geom: the source lies upstream
+    // of the slab and the detector downstream of it): source and slit widths,
+    // 1/(slit_z - src_z), the distances from the source plane to the slab's
+    // faces, the depth, the faces' half-widths less 1e-5 of themselves,
+    // 1 - cos alpha, the detector plane, its half-widths and pixels per metre,
+    // the margins (pixels) inside which a pixel edge is decided in FP64
+    // instead, the smallest direction cosine along z taken in FP32, and the
+    // weight's scale per metre
+    int32_t fast_geom;
+    float f_src_w, f_src_h, f_slit_w, f_slit_h, f_inv_dz, f_lz_in, f_lz_out, f_depth, f_half_z;
+    float f_clear_x, f_clear_y, f_omc;
+    float f_det_z, f_det_hw, f_det_hh, f_inv_px, f_inv_py, f_eps_x, f_eps_y, f_fz_min, f_wscale;
     // sample
     double size[3];               // sizes (phases are formed in FP64)
     double shell;
@@ -231,6 +243,9 @@ __device__ __forceinline__ double centred_u(uint32_t x)
     return __builtin_fma((double)x, 0x1p-32, 0x1p-33 - 0.5);
 }
 __device__ __forceinline__ double u64(uint32_t x) { return __builtin_fma((double)x, 0x1p-32, 0x1p-33); }
+// The same in FP32 (x rounded to 24 bits: absolute error below 2^-25).
+__device__ __forceinline__ float centred_uf(uint32_t x) { return __builtin_fmaf((float)x, 0x1p-32f, -0.5f); }
+__device__ __forceinline__ float uf(uint32_t x) { return __builtin_fmaf((float)x, 0x1p-32f, 0x1p-33f); }
 
 // ---------------------------------------------------------------- FP32 math
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -1630,29 +1645,27 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
 }
 
 // ---------------------------------------------------------------- one neutron
-struct Event {
-    int32_t pixel;  // -1: not tallied
-    float w;
-    float q;        // 0 when the sample is missed
+// ---------------------------------------------------------------- geometry
+// One neutron's flight (A3-A6, A12): the chord through the slab, |Q|, the
+// pixel, and what the weight and the attenuation need.
+struct Geom {
+    bool in_sample, on_det;
+    int32_t pixel;
+    float len;            // chord through the slab (m)
+    double qd;            // |Q| (1/A), FP64: the amplitudes' phases are formed from it
+    double qv[3];         // Q in the lab frame (anisotropic models)
+    float path_in;        // path inside the slab before the scattering point (m)
+    float px, py, pz;     // scattering point (m; attenuation)
+    float fx, fy, fz;     // outgoing direction (attenuation)
 };
 
-// Traces neutron i.  tab_size/tab_norm point to the LDS copies of the
-// tables; lq to the LDS copy of the quadrature nodes (QUAD mode; with
-// nparts > 1 the weight is this part's share of the exact average).
-// ATT: the sample's attenuation is compiled in (the atomic-tally and
-// per-neutron kernels; the others leave it out and the host routes attenuated
-// runs to the atomic tallies)
-template <int KIND, int MODE, bool ATT = false>
-__device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
-                                               const double* tab_size, const double* tab_norm,
-                                               const float* lq, int part = 0, int nparts = 1)
+// The flight in FP64 (the reference arithmetic of the pixel): source and
+// slit points, the slab by the z faces when the path stays clear of the side
+// faces (else the three-axis intersection), the cone about the flight
+// direction with the basis of Duff et al. (JCGT 2017), the detector plane.
+template <bool ANISO, bool ATT>
+__device__ __forceinline__ void geom_f64(const TraceArgs& a, const U4& r0, const U4& r1, Geom& g)
 {
-    Event ev{-1, 0.0f, 0.0f};
-    const uint32_t ilo = (uint32_t)i, ihi = (uint32_t)(i >> 32);
-    const U4 r0 = philox4x32_10(ilo, ihi, 0u, a.exp_id, a.seed_lo, a.seed_hi);
-    const U4 r1 = philox4x32_10(ilo, ihi, 1u, a.exp_id, a.seed_lo, a.seed_hi);
-
-    // source -> slit flight
     const double sx = centred_u(r0.x) * a.src_w, sy = centred_u(r0.y) * a.src_h;
     const double tx = centred_u(r0.z) * a.slit_w, ty = centred_u(r0.w) * a.slit_h;
     const double dx = tx - sx, dy = ty - sy, dz = a.slit_z - a.src_z;
@@ -1697,15 +1710,14 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
             }
         }
     }
-    // no early exit: a miss is carried as a flag (straight-line loop bodies
-    // keep far fewer registers live than branchy ones)
+    // no early exit: a miss is carried as a flag
     const bool in_sample = s_out > s_in;
     const double len = in_sample ? s_out - s_in : 0.0;
     const double sp = __builtin_fma(u64(r1.y), len, s_in);
     const double rx = __builtin_fma(sp, kx, sx), ry = __builtin_fma(sp, ky, sy),
                  rz = __builtin_fma(sp, kz, a.src_z);
 
-    // cone sampling about the flight direction; basis of Duff et al. (JCGT 2017)
+    // cone sampling about the flight direction
     const double t = u64(r1.z) * a.omc;
     const double c2 = 1.0 - t;
     const double s2 = sqrt_d(t * (2.0 - t));
@@ -1719,8 +1731,6 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     const double pz = cps * (-sg * kx) + sps * (-ky);
     const double fx = c2 * kx + s2 * px, fy = c2 * ky + s2 * py, fz = c2 * kz + s2 * pz;
     const double qd = k * sqrt_d(2.0 * t);
-    const float q = (float)qd;
-    ev.q = in_sample ? q : 0.0f;
 
     // detector plane and pixel
     const bool forward = fz > 0.0;
@@ -1728,27 +1738,151 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     const double xd = __builtin_fma(sd, fx, rx), yd = __builtin_fma(sd, fy, ry);
     const double fxp = floor((xd + a.det_hw) * a.inv_px);
     const double fyp = floor((yd + a.det_hh) * a.inv_py);
-    const bool on_det = in_sample && forward && fxp >= 0.0 && fxp < (double)a.nx && fyp >= 0.0
-                        && fyp < (double)a.ny;
+    g.in_sample = in_sample;
+    g.on_det = in_sample && forward && fxp >= 0.0 && fxp < (double)a.nx && fyp >= 0.0 && fyp < (double)a.ny;
+    g.pixel = g.on_det ? (int32_t)fyp * a.nx + (int32_t)fxp : -1;
+    g.len = (float)len;
+    g.qd = qd;
+    if constexpr (ANISO) {
+        g.qv[0] = k * __builtin_fma(s2, px, -t * kx);
+        g.qv[1] = k * __builtin_fma(s2, py, -t * ky);
+        g.qv[2] = k * __builtin_fma(s2, pz, -t * kz);
+    }
+    if constexpr (ATT) {
+        g.path_in = (float)(sp - s_in);
+        g.px = (float)rx;
+        g.py = (float)ry;
+        g.pz = (float)rz;
+        g.fx = (float)fx;
+        g.fy = (float)fy;
+        g.fz = (float)fz;
+    }
+}
+
+// The same flight in FP32 for isotropic models, measured from the slab rather
+// than the source (the entry point through the slopes dx/dz, dy/dz; the chord
+// as depth x |k|/k_z), which leaves no cancellation.  |Q| = k sqrt(2t) needs
+// only the wavelength and the cone draw and stays FP64 (the amplitudes' phases
+// reach tens of radians, where FP32 would lose the pixel bar's 1e-4 in
+// sparse pixels); an anisotropic model's Q vector also needs the direction to
+// better than FP32, so those models take geom_f64 throughout.  Its pixel coordinates carry an
+// error below 2e-7 m (rounding of the ~0.3 m lever arm to the detector and of
+// the direction); a neutron whose coordinates lie within the margin f_eps_x,
+// f_eps_y (6e-7 m) of a pixel edge, whose path comes near a side face of the
+// slab or whose outgoing direction is far from the beam axis is not decided
+// here (false): the caller takes geom_f64.  Every neutron decided here lands
+// in the pixel geom_f64 gives it.
+template <bool ATT>
+__device__ __forceinline__ bool geom_f32(const TraceArgs& a, const U4& r0, const U4& r1, Geom& g)
+{
+    const float sx = centred_uf(r0.x) * a.f_src_w, sy = centred_uf(r0.y) * a.f_src_h;
+    const float tx = centred_uf(r0.z) * a.f_slit_w, ty = centred_uf(r0.w) * a.f_slit_h;
+    const float mx = (tx - sx) * a.f_inv_dz, my = (ty - sy) * a.f_inv_dz;
+    // entry and exit points on the z faces
+    const float xa = __builtin_fmaf(a.f_lz_in, mx, sx), xb = __builtin_fmaf(a.f_lz_out, mx, sx);
+    const float ya = __builtin_fmaf(a.f_lz_in, my, sy), yb = __builtin_fmaf(a.f_lz_out, my, sy);
+    const bool clear = fmaxf(fabsf(xa), fabsf(xb)) < a.f_clear_x && fmaxf(fabsf(ya), fabsf(yb)) < a.f_clear_y;
+    const float g2 = __builtin_fmaf(mx, mx, __builtin_fmaf(my, my, 1.0f));
+    const float rn = __builtin_amdgcn_rsqf(g2);
+    const float kz = rn, kx = mx * rn, ky = my * rn;
+    const float len = a.f_depth * g2 * rn;                     // depth sqrt(1 + mx^2 + my^2)
+    const float u5 = uf(r1.y);
+    const float ud = u5 * a.f_depth;
+    const float rx = __builtin_fmaf(ud, mx, xa), ry = __builtin_fmaf(ud, my, ya);
+    const float rz = ud - a.f_half_z;
+
+    // cone about k: psi = 2 pi u from the quarter turns of u
+    const float t = uf(r1.z) * a.f_omc;
+    const float c2 = 1.0f - t;
+    const float s2 = __builtin_amdgcn_sqrtf(t * (2.0f - t));
+    const float u7 = 4.0f * uf(r1.w);
+    const float nq = rintf(u7);
+    float sr, cr, sps, cps;
+    sincos_poly((u7 - nq) * (float)(0.5 * kPi), sr, cr);
+    quadrant((int)nq, sr, cr, sps, cps);
+    const float aa = -rcpf(1.0f + kz);
+    const float bb = kx * ky * aa;
+    const float px = cps * __builtin_fmaf(kx * kx, aa, 1.0f) + sps * bb;
+    const float py = cps * bb + sps * __builtin_fmaf(ky * ky, aa, 1.0f);
+    const float pz = -(cps * kx + sps * ky);
+    const float fx = __builtin_fmaf(c2, kx, s2 * px), fy = __builtin_fmaf(c2, ky, s2 * py);
+    const float fz = __builtin_fmaf(c2, kz, s2 * pz);
+
+    // detector plane, pixel coordinates
+    const float sd = (a.f_det_z - rz) * rcpf(fz);
+    const float X = (__builtin_fmaf(sd, fx, rx) + a.f_det_hw) * a.f_inv_px;
+    const float Y = (__builtin_fmaf(sd, fy, ry) + a.f_det_hh) * a.f_inv_py;
+    const bool near = fabsf(X - rintf(X)) < a.f_eps_x || fabsf(Y - rintf(Y)) < a.f_eps_y;
+    const float fxp = floorf(X), fyp = floorf(Y);
+    g.in_sample = true;
+    g.on_det = fxp >= 0.0f && fxp < (float)a.nx && fyp >= 0.0f && fyp < (float)a.ny;
+    g.pixel = g.on_det ? (int32_t)fyp * a.nx + (int32_t)fxp : -1;
+    g.len = len;
+    const double lambda = __builtin_fma(a.lambda_span, 2.0 * u64(r1.x) - 1.0, a.lambda0);
+    g.qd = div_d(2.0 * kPi, lambda) * sqrt_d(2.0 * (u64(r1.z) * a.omc));
+    if constexpr (ATT) {
+        g.path_in = u5 * len;
+        g.px = rx;
+        g.py = ry;
+        g.pz = rz;
+        g.fx = fx;
+        g.fy = fy;
+        g.fz = fz;
+    }
+    return clear && !near && fz > a.f_fz_min;
+}
+
+struct Event {
+    int32_t pixel;  // -1: not tallied
+    float w;
+    float q;        // 0 when the sample is missed
+};
+
+// Traces neutron i.  tab_size/tab_norm point to the LDS copies of the
+// tables; lq to the LDS copy of the quadrature nodes (QUAD mode; with
+// nparts > 1 the weight is this part's share of the exact average).
+// ATT: the sample's attenuation is compiled in (the atomic-tally and
+// per-neutron kernels; the others leave it out and the host routes attenuated
+// runs to the atomic tallies)
+template <int KIND, int MODE, bool ATT = false>
+__device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
+                                               const double* tab_size, const double* tab_norm,
+                                               const float* lq, int part = 0, int nparts = 1)
+{
+    Event ev{-1, 0.0f, 0.0f};
+    const uint32_t ilo = (uint32_t)i, ihi = (uint32_t)(i >> 32);
+    const U4 r0 = philox4x32_10(ilo, ihi, 0u, a.exp_id, a.seed_lo, a.seed_hi);
+    const U4 r1 = philox4x32_10(ilo, ihi, 1u, a.exp_id, a.seed_lo, a.seed_hi);
+
+    Geom geo;
+    bool exact = true;
+    if constexpr (!kAniso<KIND>)
+        if (a.fast_geom) exact = !geom_f32<ATT>(a, r0, r1, geo);
+    if (exact) geom_f64<kAniso<KIND>, ATT>(a, r0, r1, geo);
+    const bool in_sample = geo.in_sample, on_det = geo.on_det;
+    const double qd = geo.qd;
+    const float q = (float)qd;
+    ev.q = in_sample ? q : 0.0f;
 
     // attenuation along the path inside the slab, before the scattering point
     // and after it along k_f to the face where it leaves (when asked for)
     float att = 1.0f;
     if (ATT && a.att_on) {
-        const double o[3] = {rx, ry, rz}, dv[3] = {fx, fy, fz}, hw[3] = {a.half_x, a.half_y, a.half_z};
-        double tout = 1e300;
+        const float o[3] = {geo.px, geo.py, geo.pz}, dv[3] = {geo.fx, geo.fy, geo.fz};
+        const float hw[3] = {(float)a.half_x, (float)a.half_y, (float)a.half_z};
+        float tout = 3.0e38f;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            if (dv[c] != 0.0) tout = fmin(tout, ((dv[c] > 0.0 ? hw[c] : -hw[c]) - o[c]) * rcp_d(dv[c]));
-        att = (float)exp(-a.mu_att * ((sp - s_in) + tout));
+            if (dv[c] != 0.0f) tout = fminf(tout, ((dv[c] > 0.0f ? hw[c] : -hw[c]) - o[c]) * rcpf(dv[c]));
+        att = expf(-(float)a.mu_att * (geo.path_in + tout));
     }
 
     // scattering vector in the lab frame (anisotropic models)
     double qvd[3] = {0.0, 0.0, 0.0};
     if constexpr (kAniso<KIND>) {
-        qvd[0] = k * __builtin_fma(s2, px, -t * kx);
-        qvd[1] = k * __builtin_fma(s2, py, -t * ky);
-        qvd[2] = k * __builtin_fma(s2, pz, -t * kz);
+        qvd[0] = geo.qv[0];
+        qvd[1] = geo.qv[1];
+        qvd[2] = geo.qv[2];
     }
     // the weight (computed for every lane: the wave runs it anyway)
     float f2;
@@ -1806,11 +1940,11 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
         // MODE 2 (surrogate): the caller multiplies by the network's <F^2>
         f2 = 1.0f;
     }
-    float w = (float)(len * a.wscale) * f2;
+    float w = geo.len * a.f_wscale * f2;
     if (a.sq_on) w *= struct_factor(a, q);
     if constexpr (ATT) w *= att;
     if (on_det) {
-        ev.pixel = (int32_t)fyp * a.nx + (int32_t)fxp;
+        ev.pixel = geo.pixel;
         ev.w = w;
     }
     return ev;

@@ -882,6 +882,31 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     a.inv_py = p->ny / p->det_h;
     a.nx = p->nx;
     a.ny = p->ny;
+    // FP32 geometry of isotropic models: the source upstream of the slab, the
+    // detector downstream
+    a.fast_geom = p->src_z < -a.half_z && p->det_z > a.half_z;
+    a.f_src_w = (float)p->src_w;
+    a.f_src_h = (float)p->src_h;
+    a.f_slit_w = (float)p->slit_w;
+    a.f_slit_h = (float)p->slit_h;
+    a.f_inv_dz = (float)(1.0 / (p->slit_z - p->src_z));
+    a.f_lz_in = (float)(-a.half_z - p->src_z);
+    a.f_lz_out = (float)(a.half_z - p->src_z);
+    a.f_depth = (float)p->sample_d;
+    a.f_half_z = (float)a.half_z;
+    a.f_clear_x = (float)(a.half_x * (1.0 - 1e-5));
+    a.f_clear_y = (float)(a.half_y * (1.0 - 1e-5));
+    a.f_omc = (float)*omc;
+    a.f_det_z = (float)p->det_z;
+    a.f_det_hw = (float)a.det_hw;
+    a.f_det_hh = (float)a.det_hh;
+    a.f_inv_px = (float)a.inv_px;
+    a.f_inv_py = (float)a.inv_py;
+    // pixel edges within 6e-7 m (three times the FP32 path's error bound) are
+    // decided in FP64
+    a.f_eps_x = (float)(6e-7 * a.inv_px);
+    a.f_eps_y = (float)(6e-7 * a.inv_py);
+    a.f_fz_min = 0.5f;
     *mean_v = host::mean_volume(p->kind, p->size, p->shell, p->poly, p->poly_mask, p->poly_kind, p->extra);
     if (p->kind == SANS_BINARY_HARD_SPHERE) {
         // the total volume fraction over the total number density
@@ -897,6 +922,7 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     // n F^2 in 1/Angstrom; a shape-independent model's cross-section is in 1/cm
     *wscale = 1e10 * dOmega * (is_shape_independent(p->kind) ? 1e-8 : p->phi / *mean_v);
     a.wscale = *wscale;
+    a.f_wscale = (float)*wscale;
     for (int k = 0; k < 3; ++k) {
         a.size[k] = p->size[k];
         a.fsize[k] = (float)p->size[k];
