@@ -164,7 +164,7 @@ def lib():
         L.orc_bf16_round.argtypes = [d]
         L.orc_bf16_round.restype = d
         L.orc_mlp_forward.argtypes = [P(d), P(d), i32, P(d), i32, P(d), P(d)]
-        L.orc_mlp_backward.argtypes = [P(d), P(d), P(d), i32, P(d), i32]
+        L.orc_mlp_backward.argtypes = [P(d), P(d), P(d), i32, P(d), i32, P(d)]
         L.orc_set_surrogate.argtypes = [P(d), P(d), P(d)]
         L.orc_trace_debug_ex.argtypes = [P(OrcParams), u64, u64, u64, u32, P(d)]
         L.orc_trace_debug_ex.restype = i32
@@ -402,24 +402,33 @@ def mlp_param_count() -> int:
     return int(lib().orc_mlp_param_count())
 
 
-def mlp_forward(w: np.ndarray, x: np.ndarray, round_bf16: bool = False) -> np.ndarray:
+def mlp_forward(w: np.ndarray, x: np.ndarray, round_bf16: bool = False, hidden: bool = False):
+    """Outputs y [n]; with hidden, also the pre-activations and activations
+    of the four hidden layers, each [4, n, 256]."""
     w = np.ascontiguousarray(w, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64)
     n = x.shape[0]
     y = np.zeros(n)
+    z = np.zeros((4, n, 256)) if hidden else None
+    h = np.zeros((4, n, 256)) if hidden else None
     lib().orc_mlp_forward(_ptr(w, C.c_double), _ptr(x, C.c_double), n, _ptr(y, C.c_double),
-                          int(round_bf16), None, None)
-    return y
+                          int(round_bf16), _ptr(z, C.c_double) if hidden else None,
+                          _ptr(h, C.c_double) if hidden else None)
+    return (y, z, h) if hidden else y
 
 
-def mlp_backward(w: np.ndarray, x: np.ndarray, dy: np.ndarray, round_bf16: bool = False) -> np.ndarray:
+def mlp_backward(w: np.ndarray, x: np.ndarray, dy: np.ndarray, round_bf16: bool = False,
+                 with_abs: bool = False):
+    """Gradient of sum(dy * y) over the parameters; with_abs, also the sum of
+    the absolute values of the terms of each element."""
     w = np.ascontiguousarray(w, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64)
     dy = np.ascontiguousarray(dy, dtype=np.float64)
     dw = np.zeros(mlp_param_count())
+    da = np.zeros(mlp_param_count()) if with_abs else None
     lib().orc_mlp_backward(_ptr(w, C.c_double), _ptr(x, C.c_double), _ptr(dy, C.c_double), x.shape[0],
-                           _ptr(dw, C.c_double), int(round_bf16))
-    return dw
+                           _ptr(dw, C.c_double), int(round_bf16), _ptr(da, C.c_double) if with_abs else None)
+    return (dw, da) if with_abs else dw
 
 
 def set_surrogate(w: np.ndarray, lo, hi) -> None:

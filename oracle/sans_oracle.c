@@ -2040,9 +2040,11 @@ void orc_mlp_forward(const double* w, const double* x, int32_t n, double* y, int
 }
 
 /* dw = gradient of sum_i dy_i y_i over the parameters (chain rule written
- * out layer by layer). */
+ * out layer by layer).  dw_abs (optional, [ORC_NP]) receives, for each
+ * element, the sum of the absolute values of the terms that form it (the
+ * scale of its rounding error). */
 void orc_mlp_backward(const double* w, const double* x, const double* dy, int32_t n, double* dw,
-                      int32_t round_bf16)
+                      int32_t round_bf16, double* dw_abs)
 {
     double* z = (double*)malloc(sizeof(double) * 4L * n * ORC_NH);
     double* h = (double*)malloc(sizeof(double) * 4L * n * ORC_NH);
@@ -2051,16 +2053,26 @@ void orc_mlp_backward(const double* w, const double* x, const double* dy, int32_
     double* gn = (double*)malloc(sizeof(double) * (long)n * ORC_NH);
     orc_mlp_forward(w, x, n, y, round_bf16, z, h);
     memset(dw, 0, sizeof(double) * ORC_NP);
+    if (dw_abs) memset(dw_abs, 0, sizeof(double) * ORC_NP);
     /* output layer */
     for (int k = 0; k < ORC_NH; ++k) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += op(h[(3L * n + i) * ORC_NH + k], round_bf16) * op(dy[i], round_bf16);
+        double s = 0.0, sa = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double t = op(h[(3L * n + i) * ORC_NH + k], round_bf16) * op(dy[i], round_bf16);
+            s += t;
+            sa += fabs(t);
+        }
         dw[ORC_OFFW4 + k] = s;
+        if (dw_abs) dw_abs[ORC_OFFW4 + k] = sa;
     }
     {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += dy[i];
+        double s = 0.0, sa = 0.0;
+        for (int i = 0; i < n; ++i) {
+            s += dy[i];
+            sa += fabs(dy[i]);
+        }
         dw[ORC_OFFW4 + ORC_NH] = s;
+        if (dw_abs) dw_abs[ORC_OFFW4 + ORC_NH] = sa;
     }
     for (int i = 0; i < n; ++i)
         for (int k = 0; k < ORC_NH; ++k)
@@ -2070,17 +2082,24 @@ void orc_mlp_backward(const double* w, const double* x, const double* dy, int32_
         int kin = l == 0 ? ORC_NIN : ORC_NH;
         for (int k = 0; k < kin; ++k)
             for (int o = 0; o < ORC_NH; ++o) {
-                double s = 0.0;
+                double s = 0.0, sa = 0.0;
                 for (int i = 0; i < n; ++i) {
                     double hin = l == 0 ? x[(long)i * ORC_NIN + k] : h[((long)(l - 1) * n + i) * ORC_NH + k];
-                    s += op(hin, round_bf16) * op(g[(long)i * ORC_NH + o], round_bf16);
+                    const double t = op(hin, round_bf16) * op(g[(long)i * ORC_NH + o], round_bf16);
+                    s += t;
+                    sa += fabs(t);
                 }
                 dw[orc_offw(l) + (long)k * ORC_NH + o] = s;
+                if (dw_abs) dw_abs[orc_offw(l) + (long)k * ORC_NH + o] = sa;
             }
         for (int o = 0; o < ORC_NH; ++o) {
-            double s = 0.0;
-            for (int i = 0; i < n; ++i) s += g[(long)i * ORC_NH + o];
+            double s = 0.0, sa = 0.0;
+            for (int i = 0; i < n; ++i) {
+                s += g[(long)i * ORC_NH + o];
+                sa += fabs(g[(long)i * ORC_NH + o]);
+            }
             dw[orc_offb(l) + o] = s;
+            if (dw_abs) dw_abs[orc_offb(l) + o] = sa;
         }
         if (l == 0) break;
         for (int i = 0; i < n; ++i)

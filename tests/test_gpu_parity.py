@@ -17,10 +17,9 @@ import torch
 
 import oracle
 from paper_2501_06054_amd import workloads as W
+from tests.parity_bars import NTHREADS, SUMMED_BAR, check_detector, check_weights, oracle_detector  # noqa: F401
 
 pytestmark = pytest.mark.gpu
-
-NTHREADS = max(1, min(16, os.cpu_count() or 1))
 
 
 def log(msg):
@@ -33,53 +32,6 @@ def S():
     from paper_2501_06054_amd import sans
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     return sans
-
-
-def check_weights(w_gpu, w_orc, where=""):
-    w_gpu = np.asarray(w_gpu, dtype=np.float64)
-    wmax = np.max(np.abs(w_orc)) if w_orc.size else 0.0
-    tol = 1e-5 * wmax + 1e-4 * np.abs(w_orc)
-    bad = np.abs(w_gpu - w_orc) > tol
-    assert not bad.any(), (f"{where}: {bad.sum()} weights out of tolerance; worst "
-                           f"{np.max(np.abs(w_gpu - w_orc) / np.maximum(tol, 1e-300)):.3g} x tol")
-
-
-def check_detector(d_gpu, d_orc, where="", count=None, w_max=None):
-    """Same hit pixels, total within 1e-6 and every hit pixel within 1e-4
-    relative.  With count (the oracle's hits per pixel) and w_max (the
-    largest single weight), a pixel may instead deviate by the sum of the
-    per-neutron bar over its neutrons, 1e-4 |pixel| + 1e-5 w_max count: the
-    bar for models whose amplitude has zeros inside the Q range (the capped
-    bodies, the thin-walled prism), where a sparse pixel can be one neutron
-    near a zero of F."""
-    d_gpu = np.asarray(d_gpu)
-    assert d_gpu.shape == d_orc.shape
-    # same set of hit pixels
-    assert np.array_equal(d_gpu != 0, d_orc != 0), f"{where}: hit patterns differ"
-    tot_g, tot_o = d_gpu.sum(), d_orc.sum()
-    assert abs(tot_g - tot_o) <= 1e-6 * abs(tot_o), f"{where}: total {tot_g} vs {tot_o}"
-    nz = d_orc != 0
-    err = np.abs(d_gpu[nz] - d_orc[nz])
-    if count is None:
-        rel = err / np.abs(d_orc[nz])
-        assert rel.max() <= 1e-4 if rel.size else True, f"{where}: worst pixel rel {rel.max():.3g}"
-    else:
-        tol = 1e-4 * np.abs(d_orc[nz]) + 1e-5 * w_max * count[nz].astype(np.float64)
-        assert (err <= tol).all(), f"{where}: worst pixel {np.max(err / tol):.3g} x the summed bar"
-
-
-# models judged pixel by pixel with the summed per-neutron bar
-SUMMED_BAR = ("barbell", "capped_cylinder", "hollow_prism", "superball", "pringle")
-
-
-def oracle_detector(p, n, seed, first=0):
-    """The oracle's detector, plus (count, w_max) for the summed bar where the
-    model needs it (w_max over the first 100003 of these neutrons)."""
-    if p["kind"] not in SUMMED_BAR:
-        return oracle.trace(p, n, seed, first=first, nthreads=NTHREADS), {}
-    ref, _, cnt = oracle.trace(p, n, seed, first=first, nthreads=NTHREADS, with_count=True)
-    _, w, _ = oracle.trace_debug(p, min(n, 100003), seed, first=first)
-    return ref, dict(count=cnt, w_max=float(np.max(np.abs(w))))
 
 
 # ------------------------------------------------------------------ streams
@@ -405,8 +357,11 @@ def test_detector_parity(S, name, tally):
 @pytest.mark.parametrize("name", ["quad_parallelepiped", "quad_capped_cylinder", "quad_hollow_prism",
                                   "quad_hollow_cylinder"])
 def test_quad_detector_parity(S, name):
+    """Exact-average mode (5776 orientation nodes per neutron), 1e5 neutrons
+    on the 128 x 128 detector."""
     p = W.workload(name)["params"]
-    n, seed = 6007, 6
+    n, seed = 100_003, 6
+    log(f"quad detector {name} n={n}")
     m = S.Model(p)
     det = m.trace(n, seed)
     torch.cuda.synchronize()
@@ -515,6 +470,22 @@ def test_full_size_coreshell(S):
     torch.cuda.synchronize()
     ref = oracle.trace(p, n, seed, nthreads=NTHREADS)
     check_detector(det.cpu().numpy(), ref, "coreshell 1e8")
+    m.close()
+
+
+@pytest.mark.parametrize("name", ["oriented_cylinder", "oriented_ellipsoid"])
+def test_full_size_oriented(S, name):
+    """The oriented cylinder and triaxial ellipsoid at their full 1e9
+    neutrons, in the launch configuration the benchmark times: the whole
+    256 x 256 detector against the oracle's."""
+    wl = W.workload(name)
+    p, n, seed = wl["params"], wl["n"], wl["seed"]
+    log(f"full-size {name} n={n} oracle threads={NTHREADS}")
+    m = S.Model(p)
+    det = m.trace(n, seed)
+    torch.cuda.synchronize()
+    ref = oracle.trace(p, n, seed, nthreads=NTHREADS)
+    check_detector(det.cpu().numpy(), ref, f"{name} 1e9")
     m.close()
 
 
