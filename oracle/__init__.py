@@ -59,6 +59,7 @@ class OrcParams(C.Structure):
         ("table_size", C.c_int32), ("quad_n", C.c_int32),
         ("poly_kind", C.c_int32), ("sq_kind", C.c_int32),
         ("extra", C.c_double * 4), ("sq_extra", C.c_double * 2), ("mu_att", C.c_double),
+        ("poly_sep", C.c_double * 3),
     ]
 
 
@@ -202,6 +203,8 @@ def to_params(p: dict) -> OrcParams:
     o.mu_att = float(p.get("mu_att", 0.0))
     for k, v in enumerate(p.get("sq_extra", (0.0, 0.0))):
         o.sq_extra[k] = float(v)
+    for k, v in enumerate(p.get("poly_sep", (0.0, 0.0, 0.0))):
+        o.poly_sep[k] = float(v)
     return o
 
 
@@ -384,10 +387,11 @@ def trace_debug(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0):
 
 
 def trace_debug_ex(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0) -> np.ndarray:
-    """Per-neutron intermediates [n, 11]: pixel, w, q, Q_x, Q_y, Q_z, y,
-    theta, phi, Psi, path length (m)."""
+    """Per-neutron intermediates [n, 14]: pixel, w, q, Q_x, Q_y, Q_z, y,
+    theta, phi, Psi, path length (m), and the independent size factors
+    y_0, y_1, y_2 (1 where a size has no width of its own)."""
     o = to_params(p)
-    out = np.zeros((n, 11))
+    out = np.zeros((n, 14))
     rc = lib().orc_trace_debug_ex(C.byref(o), first, n, seed, exp_id, _ptr(out, C.c_double))
     if rc != 0:
         raise ValueError(f"oracle trace failed ({rc})")

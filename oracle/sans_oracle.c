@@ -122,6 +122,10 @@ typedef struct {
                               depth (kT) and width (in diameters)           */
     double mu_att;         /* attenuation coefficient of the sample (1/m);
                               0 -> none                                     */
+    double poly_sep[3];    /* independent relative widths (Methods,
+                              "Polydispersity ...", Eq. (8)): size[k] times
+                              its own draw y_k ~ N(1, poly_sep[k]^2) kept
+                              where positive; 0 -> size[k] fixed            */
 } orc_params;
 
 /* Surrogate mode (mode 2): a network replaces the exact average; set with
@@ -1337,10 +1341,33 @@ static double prod_moment(const orc_params* p, const double* alpha, const double
     return total;
 }
 
+/* Any independent width set. */
+static int sep_on(const orc_params* p)
+{
+    return p->poly_sep[0] > 0.0 || p->poly_sep[1] > 0.0 || p->poly_sep[2] > 0.0;
+}
+
 /* Number-averaged particle volume <V> (n = phi/<V>). */
 double orc_mean_volume(const orc_params* p)
 {
     const double* s = p->size;
+    if (sep_on(p)) {
+        /* independent draws of the sizes: V is a product of powers of the
+           sizes for the models that take them, so <V> is V times the
+           moments <y_k^e_k>, e_k the power of size k in V */
+        int e[3] = {0, 0, 0};
+        double v;
+        switch (p->kind) {
+        case 0: v = vol_sphere(s[0]); e[0] = 3; break;
+        case 2: v = ORC_PI * s[0] * s[0] * s[1]; e[0] = 2; e[1] = 1; break;
+        case 3: v = 4.0 / 3.0 * ORC_PI * s[0] * s[1] * s[2]; e[0] = e[1] = e[2] = 1; break;
+        case 4: v = s[0] * s[1] * s[2]; e[0] = e[1] = e[2] = 1; break;
+        case 41: v = ORC_PI * s[0] * s[1] * s[2]; e[0] = e[1] = e[2] = 1; break;
+        default: return NAN;
+        }
+        for (int k = 0; k < 3; ++k) v *= truncnorm_moment(p->poly_sep[k], e[k]);
+        return v;
+    }
     int b0 = p->poly_mask & 1, b1 = p->poly_mask >> 1 & 1, b2 = p->poly_mask >> 2 & 1;
     switch (p->kind) {
     case 0:
@@ -1646,6 +1673,18 @@ double orc_amplitude(const orc_params* p, double q, const double qvec[3], double
     return amplitude(p->kind, s, p->shell, p->sld, p->extra, q, qa, qb, qc, p->quad_n);
 }
 
+/* The squared amplitude at one event with the particle's sizes given. */
+static double form_f2_sizes(const orc_params* p, const double s[3], double q, const double qvec[3],
+                            const double ang[3])
+{
+    double A[3], B[3], C[3];
+    particle_axes(ang, A, B, C);
+    double qa = qvec[0] * A[0] + qvec[1] * A[1] + qvec[2] * A[2];
+    double qb = qvec[0] * B[0] + qvec[1] * B[1] + qvec[2] * B[2];
+    double qc = qvec[0] * C[0] + qvec[1] * C[1] + qvec[2] * C[2];
+    return form_f2(p, s, q, qa, qb, qc);
+}
+
 /* The squared amplitude (micelle: scattering per particle) at one explicit
  * event, as orc_amplitude. */
 double orc_form_f2(const orc_params* p, double q, const double qvec[3], double y, const double ang[3])
@@ -1669,15 +1708,19 @@ typedef struct {
     double one_minus_cos; /* 1 - cos(alpha) */
     double prefactor;   /* solid angle * phi / <V> */
     int third_block;    /* block 2 is used */
+    int fourth_block;   /* block 3 is used (independent draws of sizes 1, 2) */
+    double* tab_sep[3]; /* positive-Gaussian knots per independent width */
     double gx[ORC_MAX_QUAD], gw[ORC_MAX_QUAD]; /* quadrature nodes (mode 1) */
 } orc_ctx;
+
 
 typedef struct {
     int32_t pixel; /* -1: no tally */
     double w;
     double q;
-    /* intermediate values, for diagnostics */
-    double qv[3], y, ang[3], len;
+    /* intermediate values, for diagnostics: the independent size factors
+       ysep (1 where a size has no width of its own) */
+    double qv[3], y, ang[3], len, ysep[3];
 } orc_event;
 
 static int ctx_init(orc_ctx* cx, const orc_params* p)
@@ -1693,13 +1736,20 @@ static int ctx_init(orc_ctx* cx, const orc_params* p)
         cx->tab_norm = (double*)malloc(sizeof(double) * M);
         orc_table_normal(M, cx->tab_norm);
     }
+    for (int k = 0; k < 3; ++k) {
+        if (p->mode == 0 && p->poly_sep[k] > 0.0) {
+            cx->tab_sep[k] = (double*)malloc(sizeof(double) * M);
+            orc_table_truncnorm(M, p->poly_sep[k], cx->tab_sep[k]);
+        }
+    }
     double sh = sin(0.5 * p->cone_alpha);
     cx->one_minus_cos = 2.0 * sh * sh;
     /* n F^2 in 1/Angstrom; a shape-independent model gives dSigma/dOmega in
      * 1/cm directly (1e-8 per Angstrom) */
     cx->prefactor = 2.0 * ORC_PI * cx->one_minus_cos
                   * (shape_independent(p->kind) ? 1e-8 : p->phi / orc_mean_volume(p));
-    cx->third_block = (p->mode == 0) && (p->poly > 0.0 || p->orient_kind != 0);
+    cx->third_block = (p->mode == 0) && (p->poly > 0.0 || p->orient_kind != 0 || sep_on(p));
+    cx->fourth_block = (p->mode == 0) && (p->poly_sep[1] > 0.0 || p->poly_sep[2] > 0.0);
     if (p->mode >= 1) {
         if (p->quad_n < 1 || p->quad_n > ORC_MAX_QUAD) return -1;
         orc_gauss_legendre(p->quad_n, cx->gx, cx->gw);
@@ -1711,6 +1761,7 @@ static void ctx_free(orc_ctx* cx)
 {
     free(cx->tab_size);
     free(cx->tab_norm);
+    for (int k = 0; k < 3; ++k) free(cx->tab_sep[k]);
 }
 
 static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_t e)
@@ -1719,15 +1770,18 @@ static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_
     orc_event ev;
     memset(&ev, 0, sizeof(ev));
     ev.pixel = -1;
-    uint32_t r0[4], r1[4], r2[4] = {0, 0, 0, 0};
+    ev.ysep[0] = ev.ysep[1] = ev.ysep[2] = 1.0;
+    uint32_t r0[4], r1[4], r2[4] = {0, 0, 0, 0}, r3[4] = {0, 0, 0, 0};
     neutron_block(seed, i, 0, e, r0);
     neutron_block(seed, i, 1, e, r1);
     if (cx->third_block) neutron_block(seed, i, 2, e, r2);
-    double u[12];
+    if (cx->fourth_block) neutron_block(seed, i, 3, e, r3);
+    double u[16];
     for (int k = 0; k < 4; ++k) {
         u[k] = orc_uniform(r0[k]);
         u[4 + k] = orc_uniform(r1[k]);
         u[8 + k] = orc_uniform(r2[k]);
+        u[12 + k] = orc_uniform(r3[k]);
     }
 
     /* source point and slit point; the neutron flies from one to the other */
@@ -1803,7 +1857,23 @@ static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_
             ang[1] = 2.0 * ORC_PI * u[10];
             ang[2] = 2.0 * ORC_PI * u[11];
         }
-        f2 = orc_form_f2(p, q, qv, y, ang);
+        if (sep_on(p)) {
+            /* independent draws: size k from word (block 2, x) for k = 0 and
+               (block 3, x), (block 3, y) for k = 1, 2 */
+            const double uk[3] = {u[8], u[12], u[13]};
+            double s[3];
+            scaled_sizes(p, y, s);
+            for (int k2 = 0; k2 < 3; ++k2) {
+                if (p->poly_sep[k2] > 0.0) {
+                    double yk = orc_table_lookup(cx->tab_sep[k2], p->table_size, uk[k2]);
+                    ev.ysep[k2] = yk < 0.0 ? 0.0 : yk;
+                    s[k2] *= ev.ysep[k2];
+                }
+            }
+            f2 = form_f2_sizes(p, s, q, qv, ang);
+        } else {
+            f2 = orc_form_f2(p, q, qv, y, ang);
+        }
     } else if (p->mode == 1) {
         f2 = pq_avg_nodes(p, q, qv, cx->gx, cx->gw);
     } else {
@@ -1869,7 +1939,7 @@ int orc_trace_debug_ex(const orc_params* p, uint64_t first, uint64_t n, uint64_t
     if (ctx_init(&cx, p) != 0) return -1;
     for (uint64_t j = 0; j < n; ++j) {
         orc_event ev = trace_one(&cx, first + j, seed, exp_id);
-        double* o = out + j * 11;
+        double* o = out + j * 14;
         o[0] = ev.pixel;
         o[1] = ev.w;
         o[2] = ev.q;
@@ -1881,6 +1951,9 @@ int orc_trace_debug_ex(const orc_params* p, uint64_t first, uint64_t n, uint64_t
         o[8] = ev.ang[1];
         o[9] = ev.ang[2];
         o[10] = ev.len;
+        o[11] = ev.ysep[0];
+        o[12] = ev.ysep[1];
+        o[13] = ev.ysep[2];
     }
     ctx_free(&cx);
     return 0;
