@@ -63,6 +63,7 @@ STEP = {
     "hollow_F": 93,      # 3 x (FP64 phase reduction, sincos, sin/x), 3 faces
     "micelle_F": 96,     # core 3 j1(x)/x, sinc, two chain series, the sum
     "cs_cyl_F": 80, "cs_ell_F": 52, "thick_box_F": 122,
+    "box_F": 33,         # parallelepiped: three sinc series, their product, volume
     "iso_orient": 0,
     "ts_I": 8, "pcoil_I": 0, "mfrac_I": 60, "shell_F": 44, "ellcyl_F": 39,
     "paracrystal_Z": 60,
@@ -124,6 +125,11 @@ PATHS = {
     "oriented_belt_bicelle": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
                              + ["qvec"] + ["orient_angle"] * 3 + ["project_abc", "belt_F"],
     "adsorbed_layer": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["ads_I"],
+    # independent size draws: a fourth Philox block, one table lerp per size
+    "poly_sep_cylinder": COMMON + ["philox_block"] * 4 + ["uniform"] * 12
+                         + ["size_draw"] * 2 + ["qvec"] + ["orient_angle"] * 2 + ["project_c", "cylinder_F"],
+    "poly_sep_parallelepiped": COMMON + ["philox_block"] * 4 + ["uniform"] * 14
+                               + ["size_draw"] * 3 + ["qvec", "iso_orient", "project_abc", "box_F"],
     "oriented_pringle": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
                         + ["qvec", "iso_orient", "project_abc"] + ["pr_node"] * 512,
 }
