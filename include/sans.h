@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SANS_ABI_VERSION 5u
+#define SANS_ABI_VERSION 6u
 
 /* Status codes. */
 #define SANS_OK 0
@@ -394,6 +394,23 @@ typedef struct {
                                 or XCD when asked for), whatever `tally`
                                 asks; the batched launch and the surrogate
                                 mode refuse them (SANS_E_UNSUPPORTED)       */
+    double poly_sep[3];      /* independent relative widths (the paper's rule,
+                                Methods, "Polydispersity and orientational
+                                distributions", Eq. (8): each radius or
+                                length drawn from its own Gaussian; the
+                                cylinder's parameter vector carries separate
+                                spreads of r and L): size[k] is multiplied by
+                                its own y_k ~ N(1, poly_sep[k]^2) kept where
+                                positive (inverse CDF), y_0 from the word the
+                                single draw uses, y_1 and y_2 from a fourth
+                                Philox block.  All 0: none.  Otherwise
+                                Monte Carlo mode only, poly = 0 and poly_kind
+                                SANS_POLY_GAUSSIAN, for the sphere (k = 0),
+                                cylinder (k <= 1), ellipsoid,
+                                parallelepiped and elliptical cylinder
+                                (k <= 2), whose volumes are products of
+                                powers of the sizes (<V> = V prod <y_k^e_k>);
+                                the batched launch refuses it              */
 } sans_params;
 
 typedef struct sans_model_s* sans_model_t;

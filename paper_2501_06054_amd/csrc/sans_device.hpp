@@ -101,6 +101,10 @@ struct TraceArgs {
     float contrast;               // drho = sld[0] - sld[2]
     float cs_core, cs_shell;      // core-shell: sld0 - sld1, sld1 - sld2
     int32_t poly_on, poly_mask, orient_kind, third_block;
+    // independent size draws: sep_on[k] for size k (its table in tab_sep +
+    // k M, global memory), sep_block3 when sizes 1 or 2 draw (fourth block)
+    int32_t sep_any, sep_on[3], sep_block3;
+    const double* tab_sep;
     int32_t sq_on, sq_kind;       // sq_kind: 0 hard spheres, 1 adhesive, 2 square well
     float sq_2r, sq_24phi;
     float py_alpha, py_beta, py_gamma;
@@ -639,6 +643,13 @@ template <int KIND>
 constexpr bool kOneAxis = KIND == kCylinder || KIND == kBarbell || KIND == kCappedCylinder
                           || KIND == kHollowCylinder || KIND == kCoreShellCylinder || KIND == kCoreShellBicelle
                           || KIND == kStackedDisks;
+
+// Models that take independent size draws (volumes that are products of
+// powers of the sizes): sphere, cylinder, ellipsoid, parallelepiped,
+// elliptical cylinder.
+template <int KIND>
+constexpr bool kSepKind = KIND == kSphere || KIND == kCylinder || KIND == kEllipsoid || KIND == kParallelepiped
+                          || KIND == kEllipticalCylinder;
 
 // The caps' part of the barbell / capped-cylinder amplitude (Tables I-II,
 // group A), in FP32: sum_i w_i cos(P + B t_i) 2J1(X s_i)/(X s_i) over the
@@ -1214,14 +1225,15 @@ __device__ __forceinline__ float lattice_factor(const TraceArgs& a, double q, do
 }
 
 // F of one drawn particle (MC mode).  y scales the sizes selected by the
-// polydispersity mask; q, qa, qb, qc are |Q| and its projections (FP64).
+// polydispersity mask, ys[k] size k (independent draws; 1 when off); q, qa,
+// qb, qc are |Q| and its projections (FP64).
 template <int KIND>
-__device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, double q, double qa,
-                                              double qb, double qc)
+__device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, const double ys[3], double q,
+                                              double qa, double qb, double qc)
 {
     double s[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) s[c] = (a.poly_mask >> c & 1) ? a.size[c] * y : a.size[c];
+    for (int c = 0; c < 3; ++c) s[c] = ((a.poly_mask >> c & 1) ? a.size[c] * y : a.size[c]) * ys[c];
     constexpr float k43pi = (float)(4.0 / 3.0 * kPi);
     if constexpr (KIND == kSphere) {
         const float r = (float)s[0];
@@ -1889,10 +1901,23 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     float f2;
     if constexpr (MODE == 0) {
         double y = 1.0;
+        double ys[3] = {1.0, 1.0, 1.0};   // independent size draws (1 when off)
         Trig3 g{a.ang_sin[0], a.ang_cos[0], a.ang_sin[1], a.ang_cos[1], a.ang_sin[2], a.ang_cos[2]};
         if (a.third_block) {
             const U4 r2 = philox4x32_10(ilo, ihi, 2u, a.exp_id, a.seed_lo, a.seed_hi);
             if (a.poly_on) y = fmax(table_lerp(tab_size, a.M, u64(r2.x)), 0.0);
+            // independent size draws: size 0 from (block 2, x), sizes 1 and 2
+            // from (block 3, x) and (block 3, y)
+            if constexpr (kSepKind<KIND>) {
+                if (a.sep_any) {
+                    if (a.sep_on[0]) ys[0] = fmax(table_lerp(a.tab_sep, a.M, u64(r2.x)), 0.0);
+                    if (a.sep_block3) {
+                        const U4 r3 = philox4x32_10(ilo, ihi, 3u, a.exp_id, a.seed_lo, a.seed_hi);
+                        if (a.sep_on[1]) ys[1] = fmax(table_lerp(a.tab_sep + a.M, a.M, u64(r3.x)), 0.0);
+                        if (a.sep_on[2]) ys[2] = fmax(table_lerp(a.tab_sep + 2 * a.M, a.M, u64(r3.y)), 0.0);
+                    }
+                }
+            }
             if constexpr (kAniso<KIND>) {
                 if (a.orient_kind == 1) {
                     rotate_by(a.ang_sin[0], a.ang_cos[0],
@@ -1930,7 +1955,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
         } else if constexpr (kSphereFamily<KIND>) {
             f2 = sphere_family_f2<KIND>(a, (a.poly_mask & 1) ? a.size[0] * y : a.size[0], qd);
         } else {
-            const float f = amplitude_mc<KIND>(a, y, qd, qa, qb, qc);
+            const float f = amplitude_mc<KIND>(a, y, ys, qd, qa, qb, qc);
             f2 = f * f;
             if constexpr (kLattice<KIND>) f2 *= lattice_factor<KIND>(a, qd, qa, qb, qc);
         }

@@ -327,6 +327,8 @@ struct sans_model_s {
     std::vector<float> h_quad;
     double* d_tab_size = nullptr;
     double* d_tab_norm = nullptr;
+    std::vector<double> h_tab_sep;
+    double* d_tab_sep = nullptr;   // independent size widths' tables [3][M]
     float* d_quad = nullptr;
     float* d_caps = nullptr;   // node rule (capped bodies, superball) and structure-factor constants
     double* d_replicas = nullptr;
@@ -782,6 +784,30 @@ int validate(const sans_params* p)
     if (p->poly_mask < 0 || p->poly_mask > 7) return fail(SANS_E_INVALID_ARG, "poly_mask must be in 0..7");
     if (p->poly_kind != SANS_POLY_SCHULZ && p->poly_kind != SANS_POLY_GAUSSIAN)
         return fail(SANS_E_UNSUPPORTED, "unknown poly_kind");
+    bool sep = false;
+    for (int k = 0; k < 3; ++k) {
+        if (!(p->poly_sep[k] >= 0.0 && p->poly_sep[k] <= 1.0))
+            return fail(SANS_E_INVALID_ARG, "poly_sep must be in [0, 1]");
+        if (p->poly_sep[k] > 0.0 && p->poly_sep[k] < 1e-4)
+            return fail(SANS_E_INVALID_ARG, "poly_sep must be 0 or >= 1e-4");
+        sep |= p->poly_sep[k] > 0.0;
+    }
+    if (sep) {
+        // sizes each model takes independent widths for
+        const int nsep = p->kind == SANS_SPHERE ? 1
+                       : p->kind == SANS_CYLINDER ? 2
+                       : (p->kind == SANS_ELLIPSOID || p->kind == SANS_PARALLELEPIPED
+                          || p->kind == SANS_ELLIPTICAL_CYLINDER) ? 3 : 0;
+        if (nsep == 0)
+            return fail(SANS_E_UNSUPPORTED, "poly_sep: sphere, cylinder, ellipsoid, parallelepiped or "
+                                            "elliptical cylinder only");
+        for (int k = nsep; k < 3; ++k)
+            if (p->poly_sep[k] > 0.0) return fail(SANS_E_INVALID_ARG, "poly_sep: this model has no such size");
+        if (p->mode != SANS_MODE_MC) return fail(SANS_E_UNSUPPORTED, "poly_sep: Monte Carlo mode only");
+        if (p->poly > 0.0) return fail(SANS_E_INVALID_ARG, "poly_sep: poly must be 0");
+        if (p->poly_kind != SANS_POLY_GAUSSIAN)
+            return fail(SANS_E_UNSUPPORTED, "poly_sep: the positive Gaussian (SANS_POLY_GAUSSIAN) only");
+    }
     if (p->table_size < 64 || p->table_size > 8192)
         return fail(SANS_E_INVALID_ARG, "table_size must be in 64..8192");
     for (int k = 0; k < 3; ++k) {
@@ -908,6 +934,22 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     a.f_eps_y = (float)(6e-7 * a.inv_py);
     a.f_fz_min = 0.5f;
     *mean_v = host::mean_volume(p->kind, p->size, p->shell, p->poly, p->poly_mask, p->poly_kind, p->extra);
+    if (p->poly_sep[0] > 0.0 || p->poly_sep[1] > 0.0 || p->poly_sep[2] > 0.0) {
+        // independent draws: V is a product of powers e_k of the sizes, so
+        // <V> = V prod_k <y_k^e_k>
+        const double* s = p->size;
+        double v = 0.0;
+        int e[3] = {1, 1, 1};
+        switch (p->kind) {
+        case SANS_SPHERE: v = 4.0 / 3.0 * kPi * s[0] * s[0] * s[0]; e[0] = 3; e[1] = e[2] = 0; break;
+        case SANS_CYLINDER: v = kPi * s[0] * s[0] * s[1]; e[0] = 2; e[2] = 0; break;
+        case SANS_ELLIPSOID: v = 4.0 / 3.0 * kPi * s[0] * s[1] * s[2]; break;
+        case SANS_PARALLELEPIPED: v = s[0] * s[1] * s[2]; break;
+        default: v = kPi * s[0] * s[1] * s[2]; break;   // elliptical cylinder
+        }
+        for (int k = 0; k < 3; ++k) v *= host::positive_normal_moment(p->poly_sep[k], e[k]);
+        *mean_v = v;
+    }
     if (p->kind == SANS_BINARY_HARD_SPHERE) {
         // the total volume fraction over the total number density
         const double v1 = 4.0 / 3.0 * kPi * p->size[0] * p->size[0] * p->size[0];
@@ -1124,7 +1166,10 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     a.poly_mask = p->poly_mask;
     a.orient_kind = p->orient_kind;
     const bool aniso = is_aniso(p->kind);
-    a.third_block = p->mode == SANS_MODE_MC && (a.poly_on || (aniso && p->orient_kind != 0));
+    for (int k = 0; k < 3; ++k) a.sep_on[k] = p->mode == SANS_MODE_MC && p->poly_sep[k] > 0.0;
+    a.sep_any = a.sep_on[0] || a.sep_on[1] || a.sep_on[2];
+    a.sep_block3 = a.sep_on[1] || a.sep_on[2];
+    a.third_block = p->mode == SANS_MODE_MC && (a.poly_on || (aniso && p->orient_kind != 0) || a.sep_any);
     a.sq_on = p->sq_phi > 0.0;
     if (a.sq_on) {
         double c[kPySeriesTerms], abg[3];
@@ -1195,6 +1240,21 @@ int configure(sans_model_s* m, const sans_params* p)
                               hipMemcpyHostToDevice));
         }
         a.tab_norm = m->d_tab_norm;
+    }
+    if (a.sep_any) {
+        // one positive-Gaussian table per independent width, [3][M] (rows of
+        // sizes without a width are not read)
+        const int M = p->table_size;
+        m->h_tab_sep.assign((size_t)3 * M, 1.0);
+        for (int k = 0; k < 3; ++k)
+            if (a.sep_on[k])
+                for (int j = 0; j < M; ++j)
+                    m->h_tab_sep[(size_t)k * M + j] = host::positive_normal_quantile((j + 0.5) / M, p->poly_sep[k]);
+        if (m->d_tab_sep) HIP_TRY(hipFree(m->d_tab_sep));
+        m->d_tab_sep = nullptr;
+        HIP_TRY(hipMalloc(&m->d_tab_sep, sizeof(double) * 3 * M));
+        HIP_TRY(hipMemcpy(m->d_tab_sep, m->h_tab_sep.data(), sizeof(double) * 3 * M, hipMemcpyHostToDevice));
+        a.tab_sep = m->d_tab_sep;
     }
 
     // the end caps' rule or the superball's nested rule (every mode), then the
@@ -1527,6 +1587,7 @@ int sans_model_destroy(sans_model_t m)
     if (!m) return SANS_OK;
     if (m->d_tab_size) (void)hipFree(m->d_tab_size);
     if (m->d_tab_norm) (void)hipFree(m->d_tab_norm);
+    if (m->d_tab_sep) (void)hipFree(m->d_tab_sep);
     if (m->d_quad) (void)hipFree(m->d_quad);
     if (m->d_caps) (void)hipFree(m->d_caps);
     if (m->d_replicas) (void)hipFree(m->d_replicas);
@@ -2061,6 +2122,8 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
         int rc = validate(&p[e]);
         if (rc == SANS_OK && p[e].mu_att > 0.0)
             rc = fail(SANS_E_UNSUPPORTED, "batched launch: no attenuation (trace attenuated experiments one by one)");
+        if (rc == SANS_OK && (p[e].poly_sep[0] > 0.0 || p[e].poly_sep[1] > 0.0 || p[e].poly_sep[2] > 0.0))
+            rc = fail(SANS_E_UNSUPPORTED, "batched launch: no independent size widths");
         if (rc) return rc;
         if (p[e].mode != SANS_MODE_MC) return fail(SANS_E_UNSUPPORTED, "batch: Monte Carlo mode only");
         if (p[e].nx != nx || p[e].ny != ny) return fail(SANS_E_INVALID_ARG, "batch: detectors must match");

@@ -15,7 +15,7 @@ import torch  # loaded first so that libsans shares PyTorch's HIP runtime
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsans.so")
 
-SANS_ABI_VERSION = 5
+SANS_ABI_VERSION = 6
 SANS_OK = 0
 SANS_E_INVALID_ARG = -1
 SANS_E_UNSUPPORTED = -2
@@ -70,6 +70,7 @@ class sans_params(C.Structure):
         ("nx", C.c_int32), ("ny", C.c_int32), ("quad_n", C.c_int32), ("tally", C.c_int32),
         ("poly_kind", C.c_int32), ("sq_kind", C.c_int32),
         ("extra", C.c_double * 4), ("sq_extra", C.c_double * 2), ("mu_att", C.c_double),
+        ("poly_sep", C.c_double * 3),
     ]
 
 
@@ -177,6 +178,8 @@ def to_params(p: dict, tally: str = "auto") -> sans_params:
     s.mu_att = float(p.get("mu_att", 0.0))
     for k, v in enumerate(p.get("sq_extra", (0.0, 0.0))):
         s.sq_extra[k] = float(v)
+    for k, v in enumerate(p.get("poly_sep", (0.0, 0.0, 0.0))):
+        s.poly_sep[k] = float(v)
     return s
 
 

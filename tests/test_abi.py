@@ -63,6 +63,15 @@ def _create_status(S, p):
     (dict(kind="cylinder", size=(20.0, 0.0, 0.0)), -1),
     (dict(mode="surrogate"), -2),
     (dict(kind="cylinder", size=(20.0, 40.0, 0.0), mode="quad", orient_kind="gaussian"), -2),
+    # independent size widths: the models, mode, distribution and sizes that take them
+    (dict(kind="core_shell", size=(40.0, 0, 0), shell=10.0, poly_kind="gaussian", poly_sep=(0.2, 0, 0)), -2),
+    (dict(kind="cylinder", size=(20.0, 40.0, 0.0), poly_kind="gaussian", poly_sep=(0.1, 0.1, 0.1)), -1),
+    (dict(kind="cylinder", size=(20.0, 40.0, 0.0), poly_kind="gaussian", poly_sep=(0.1, 0.1, 0), poly=0.1), -1),
+    (dict(kind="cylinder", size=(20.0, 40.0, 0.0), poly_sep=(0.1, 0.1, 0)), -2),
+    (dict(kind="cylinder", size=(20.0, 40.0, 0.0), poly_kind="gaussian", poly_sep=(0.1, 0.1, 0),
+          mode="quad", orient_kind="isotropic"), -2),
+    (dict(kind="sphere", poly_kind="gaussian", poly_sep=(-0.1, 0, 0)), -1),
+    (dict(kind="sphere", poly_kind="gaussian", poly_sep=(1.5, 0, 0)), -1),
 ])
 def test_invalid_params_rejected_without_gpu(S, over, status):
     from paper_2501_06054_amd import workloads as W

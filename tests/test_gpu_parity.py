@@ -295,6 +295,16 @@ PER_NEUTRON = {
                                                  sld=(3e-6, 0.5e-6, 6.3e-6), phi=0.25, extra=(0.01, 0, 0, 0)), 30011),
     "adsorbed_layer": (W.params(kind="adsorbed_layer", size=(2000.0, 0, 0), shell=2.5, sld=(1.5e-6, 0, 6.3e-6),
                                 extra=(12.0, 0, 0, 0), phi=0.05), 30011),
+    # independent positive-Gaussian widths per size (the paper's Eq. (8))
+    "poly_sep_cylinder": (W.workload("poly_sep_cylinder")["params"], 30011),
+    "poly_sep_parallelepiped": (W.workload("poly_sep_parallelepiped")["params"], 30011),
+    "poly_sep_sphere": (W.params(kind="sphere", size=(60.0, 0, 0), poly_kind="gaussian",
+                                 poly_sep=(0.3, 0.0, 0.0)), 20011),
+    "poly_sep_ellipsoid_gauss": (W.params(kind="ellipsoid", size=(20.0, 40.0, 120.0), poly_kind="gaussian",
+                                          poly_sep=(0.2, 0.1, 0.05), orient_kind="gaussian",
+                                          orient_mean=(1.2, 0.4, 0.8), orient_sigma=(0.2, 0.1, 0.3)), 20011),
+    "poly_sep_ellcyl_iso": (W.params(kind="elliptical_cylinder", size=(20.0, 35.0, 300.0), poly_kind="gaussian",
+                                     poly_sep=(0.1, 0.0, 0.2), orient_kind="isotropic"), 20011),
     # sample attenuation
     "attenuated_coreshell": (dict(W.workload("coreshell_py")["params"], mu_att=150.0), 30011),
     "attenuated_wide_cone_cylinder": (W.params(kind="cylinder", size=(20.0, 200.0, 0), orient_kind="isotropic",
@@ -337,7 +347,8 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "mass_surface_fractal", "gel_fit", "sticky_coreshell", "square_well_poly_sphere",
              "oriented_superball", "lamellar_caille", "lamellar_hg", "lamellar_stack_paracrystal",
              "belt_bicelle_gauss", "raspberry_poly", "pearl_necklace", "binary_hard_sphere",
-             "adsorbed_layer", "pringle_iso", "attenuated_coreshell"]
+             "adsorbed_layer", "pringle_iso", "attenuated_coreshell", "poly_sep_cylinder",
+             "poly_sep_parallelepiped", "poly_sep_ellipsoid_gauss"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -486,6 +497,21 @@ def test_full_size_oriented(S, name):
     torch.cuda.synchronize()
     ref = oracle.trace(p, n, seed, nthreads=NTHREADS)
     check_detector(det.cpu().numpy(), ref, f"{name} 1e9")
+    m.close()
+
+
+@pytest.mark.parametrize("name", ["poly_sep_cylinder", "poly_sep_parallelepiped"])
+def test_full_size_independent_widths(S, name):
+    """The independent-width workloads at their full 1e8 neutrons: the whole
+    detector against the oracle's."""
+    wl = W.workload(name)
+    p, n, seed = wl["params"], wl["n"], wl["seed"]
+    log(f"full-size {name} n={n}")
+    m = S.Model(p)
+    det = m.trace(n, seed)
+    torch.cuda.synchronize()
+    ref = oracle.trace(p, n, seed, nthreads=NTHREADS)
+    check_detector(det.cpu().numpy(), ref, f"{name} 1e8")
     m.close()
 
 
