@@ -167,6 +167,8 @@ def lib():
         L.orc_mlp_forward.argtypes = [P(d), P(d), i32, P(d), i32, P(d), P(d)]
         L.orc_mlp_backward.argtypes = [P(d), P(d), P(d), i32, P(d), i32, P(d)]
         L.orc_set_surrogate.argtypes = [P(d), P(d), P(d)]
+        L.orc_surrogate_judge.argtypes = [P(OrcParams), d, i32, P(d)]
+        L.orc_surrogate_judge.restype = i32
         L.orc_trace_debug_ex.argtypes = [P(OrcParams), u64, u64, u64, u32, P(d)]
         L.orc_trace_debug_ex.restype = i32
         _LIB = L
@@ -442,3 +444,16 @@ def set_surrogate(w: np.ndarray, lo, hi) -> None:
     lo = np.ascontiguousarray(lo, dtype=np.float64)
     hi = np.ascontiguousarray(hi, dtype=np.float64)
     lib().orc_set_surrogate(_ptr(w, C.c_double), _ptr(lo, C.c_double), _ptr(hi, C.c_double))
+
+
+def surrogate_judge(p: dict, tol: float, nbins: int):
+    """The in-domain judge of the surrogate set by set_surrogate for the
+    parameter set p: (number of flagged bins, the ln-errors at the bins'
+    edges and midpoints [2 nbins + 1]).  Later surrogate-mode traces send the
+    neutrons of flagged bins to the exact average."""
+    o = to_params(p)
+    err = np.zeros(2 * nbins + 1)
+    k = lib().orc_surrogate_judge(C.byref(o), tol, nbins, _ptr(err, C.c_double))
+    if k < 0:
+        raise ValueError("surrogate judge: no network set or bad arguments")
+    return int(k), err

@@ -2203,6 +2203,12 @@ void orc_mlp_backward(const double* w, const double* x, const double* dy, int32_
 static double g_sur_w[ORC_NP];
 static double g_sur_lo[4], g_sur_hi[4];
 static int g_sur_set = 0;
+/* the in-domain judge: bins of ln(q s0) over [lo_0, hi_0] in which the
+   network was found more than the tolerance away from the exact average;
+   neutrons in them take the exact average */
+#define ORC_MAX_JUDGE_BINS 65536
+static unsigned char g_judge_flag[ORC_MAX_JUDGE_BINS];
+static int g_judge_bins = 0;
 
 void orc_set_surrogate(const double* w, const double* lo, const double* hi)
 {
@@ -2212,19 +2218,85 @@ void orc_set_surrogate(const double* w, const double* lo, const double* hi)
         g_sur_hi[k] = hi[k];
     }
     g_sur_set = 1;
+    g_judge_bins = 0;
+}
+
+/* The network's inputs for this parameter set at x0 = ln(q s0) (u as in
+   surrogate_f2); 0 when the model's own shape lies outside the box. */
+static int surrogate_u(const orc_params* p, double x0, double u[8])
+{
+    double x[4] = {x0, log(p->size[1] / p->size[0]), log(p->size[2] / p->size[0]), p->poly};
+    for (int k = 0; k < 8; ++k) u[k] = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        if (!(x[k] >= g_sur_lo[k] - (k ? 1e-6 : 0.0) && x[k] <= g_sur_hi[k] + (k ? 1e-6 : 0.0))) return 0;
+        u[k] = g_sur_hi[k] > g_sur_lo[k] ? (2.0 * x[k] - g_sur_lo[k] - g_sur_hi[k]) / (g_sur_hi[k] - g_sur_lo[k]) : 0.0;
+    }
+    return 1;
+}
+
+/* ln of the surrogate's <F^2>(q) over the exact one at x0 = ln(q s0). */
+static double surrogate_log_error(const orc_params* p, double x0, const double* gx, const double* gw)
+{
+    double u[8], y;
+    if (!surrogate_u(p, x0, u)) return 0.0;
+    orc_mlp_forward(g_sur_w, u, 1, &y, 1, NULL, NULL);
+    const double q = exp(x0) / p->size[0];
+    orc_params p1 = *p;
+    p1.mode = 1;
+    double qv0[3] = {0.0, 0.0, 0.0};
+    const double f2_0 = pq_avg_nodes(&p1, 0.0, qv0, gx, gw);
+    const double rg2 = (p->size[0] * p->size[0] + p->size[1] * p->size[1] + p->size[2] * p->size[2])
+                     / (p->kind == 4 ? 12.0 : 5.0);
+    const double t = 1.0 + q * q * rg2 / 6.0;
+    const double sur = f2_0 * exp(y) / (t * t);
+    return log(sur / pq_avg_nodes(&p1, q, qv0, gx, gw));
+}
+
+/* The judge for parameter set p: the surrogate's ln-error at the edges and
+   midpoints of nbins bins of x0 over [lo_0, hi_0] (err [2 nbins + 1],
+   optional); a bin is flagged when the error at any of its three points
+   exceeds tol, and its neutrons then take the exact average.  Returns the
+   number of flagged bins (-1 on bad arguments). */
+int32_t orc_surrogate_judge(const orc_params* p, double tol, int32_t nbins, double* err)
+{
+    if (!g_sur_set || nbins < 1 || nbins > ORC_MAX_JUDGE_BINS || p->quad_n < 1 || p->quad_n > ORC_MAX_QUAD)
+        return -1;
+    double gx[ORC_MAX_QUAD], gw[ORC_MAX_QUAD];
+    orc_gauss_legendre(p->quad_n, gx, gw);
+    const double lo = g_sur_lo[0], hi = g_sur_hi[0];
+    double prev = fabs(surrogate_log_error(p, lo, gx, gw));
+    if (err) err[0] = prev;
+    int32_t flagged = 0;
+    for (int b = 0; b < nbins; ++b) {
+        const double xm = lo + (hi - lo) * (b + 0.5) / nbins, xe = lo + (hi - lo) * (b + 1.0) / nbins;
+        const double em = fabs(surrogate_log_error(p, xm, gx, gw)), ee = fabs(surrogate_log_error(p, xe, gx, gw));
+        if (err) {
+            err[2 * b + 1] = em;
+            err[2 * b + 2] = ee;
+        }
+        g_judge_flag[b] = prev > tol || em > tol || ee > tol;
+        flagged += g_judge_flag[b];
+        prev = ee;
+    }
+    g_judge_bins = nbins;
+    return flagged;
 }
 
 static double surrogate_f2(const orc_params* p, double q, int* in_domain)
 {
-    double x[4] = {log(q * p->size[0]), log(p->size[1] / p->size[0]), log(p->size[2] / p->size[0]), p->poly};
+    const double x0 = log(q * p->size[0]);
     *in_domain = 0;
     if (!g_sur_set) return 0.0;
     /* trained on Schulz sizes that scale all three axes together only */
     if (p->poly > 0.0 && (p->poly_kind != 0 || (p->poly_mask & 7) != 7)) return 0.0;
-    double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < 4; ++k) {
-        if (!(x[k] >= g_sur_lo[k] - (k ? 1e-6 : 0.0) && x[k] <= g_sur_hi[k] + (k ? 1e-6 : 0.0))) return 0.0;
-        u[k] = g_sur_hi[k] > g_sur_lo[k] ? (2.0 * x[k] - g_sur_lo[k] - g_sur_hi[k]) / (g_sur_hi[k] - g_sur_lo[k]) : 0.0;
+    double u[8];
+    if (!surrogate_u(p, x0, u)) return 0.0;
+    if (g_judge_bins > 0) {
+        /* the judge's bin of x0 */
+        double fb = floor((x0 - g_sur_lo[0]) / (g_sur_hi[0] - g_sur_lo[0]) * g_judge_bins);
+        if (fb < 0.0) fb = 0.0;
+        if (fb > g_judge_bins - 1) fb = g_judge_bins - 1;
+        if (g_judge_flag[(int)fb]) return 0.0;
     }
     *in_domain = 1;
     double y;

@@ -129,3 +129,58 @@ def test_partial_size_mask_takes_the_exact_average(mask):
     d7 = oracle.trace(p7, n, seed, nthreads=4)
     d7q = oracle.trace(dict(p7, mode="quad"), n, seed, nthreads=4)
     assert not np.allclose(d7, d7q, rtol=1e-3)
+
+
+# ---------------------------------------------------------------- the in-domain judge
+
+def _judged_setup(seed=11):
+    p = dict(W.workload("quad_parallelepiped")["params"], mode="surrogate", quad_n=24)
+    w = random_network(seed, bias=0.05) * 0.2
+    lo, hi = W.SURROGATE_BOX["parallelepiped"]
+    return p, w, lo, hi
+
+
+def test_judge_everywhere_gives_the_exact_average():
+    """tol = 0 flags every bin: the surrogate mode's weights are then the
+    quadrature mode's, bit for bit; tol = infinity flags none and leaves the
+    unjudged surrogate."""
+    p, w, lo, hi = _judged_setup()
+    n, seed = 600, 5
+    oracle.set_surrogate(w, lo, hi)
+    _, w_free, _ = oracle.trace_debug(p, n, seed)
+    k, _ = oracle.surrogate_judge(p, 0.0, 64)
+    assert k == 64
+    pix, w_all, _ = oracle.trace_debug(p, n, seed)
+    qpix, w_quad, _ = oracle.trace_debug(dict(p, mode="quad"), n, seed)
+    assert np.array_equal(pix, qpix)
+    assert np.array_equal(w_all, w_quad)
+    k, _ = oracle.surrogate_judge(p, math.inf, 64)
+    assert k == 0
+    _, w_none, _ = oracle.trace_debug(p, n, seed)
+    assert np.array_equal(w_none, w_free)
+    assert not np.allclose(w_free, w_quad, rtol=1e-3)   # the untrained network is far off
+
+
+def test_judge_bounds_the_error_of_what_it_keeps():
+    """A finite tolerance: neutrons of flagged bins take the exact weight;
+    the others keep the network's, within the tolerance at their bin's edges
+    and midpoint (and, the bins being fine, within twice it anywhere)."""
+    p, w, lo, hi = _judged_setup()
+    oracle.set_surrogate(w, lo, hi)
+    nb = 256
+    _, err = oracle.surrogate_judge(p, math.inf, nb)
+    tol = float(np.quantile(err, 0.5))
+    k, _ = oracle.surrogate_judge(p, tol, nb)
+    assert 0 < k < nb
+    n, seed = 1500, 6
+    pix, w_j, q = oracle.trace_debug(p, n, seed)
+    _, w_x, _ = oracle.trace_debug(dict(p, mode="quad"), n, seed)
+    hit = pix >= 0
+    x0 = np.log(q[hit] * p["size"][0])
+    b = np.clip(np.floor((x0 - lo[0]) / (hi[0] - lo[0]) * nb).astype(int), 0, nb - 1)
+    bin_err = np.maximum.reduce([err[2 * b], err[2 * b + 1], err[2 * b + 2]])
+    flagged = bin_err > tol
+    r = np.abs(np.log(w_j[hit] / w_x[hit]))
+    assert np.all(r[flagged] == 0.0)
+    assert np.all(r[~flagged] <= 2.0 * tol), float(np.max(r[~flagged]))
+    assert flagged.any() and (~flagged).any()
