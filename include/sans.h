@@ -595,6 +595,23 @@ const char* sans_mlp_last_error(void);
 int sans_model_attach_surrogate(sans_model_t m, const void* w_bf16, const float* domain_lo,
                                 const float* domain_hi);
 
+/* The exact quadrature as the network's in-domain judge (synchronous).  On
+ * the model's own line of inputs (its size ratios and width fixed, ln(q
+ * size[0]) over the box) the network's output is compared with the exact
+ * average's training target (sans_pq_dataset) at the edges and midpoints of
+ * nbins equal bins of ln(q size[0]); every bin where the two differ by more
+ * than tol (in ln <F^2>) at any of its three points is flagged, and
+ * in-domain neutrons whose ln(q size[0]) (FP64) falls in a flagged bin are
+ * queued for the exact pass like out-of-domain ones.  Attaching a network
+ * runs this judge with tol = 1e-3 and 2048 bins; calling it again replaces
+ * the flags (tol = infinity: no neutron leaves the network).
+ *   err    host float [2 nbins + 1] or NULL: |network - exact| at the points
+ *   flags  host uint8 [nbins] or NULL: 1 = the bin takes the exact average
+ * Errors: SANS_E_INVALID_ARG (nbins outside 1..65536, tol < 0 or NaN),
+ * SANS_E_UNSUPPORTED (no network attached).  A model whose own shape lies
+ * outside the box takes the exact average throughout and gets no flags. */
+int sans_model_judge_surrogate(sans_model_t m, double tol, int32_t nbins, float* err, uint8_t* flags);
+
 /* Training targets: out[i] = ln(<F^2>(q) / <F^2>(0)) - ln P_ref(q) (P_ref as
  * for sans_model_attach_surrogate) of an isotropically
  * oriented particle (kind SANS_ELLIPSOID: of revolution, 1D orientation

@@ -1849,6 +1849,7 @@ struct Event {
     int32_t pixel;  // -1: not tallied
     float w;
     float q;        // 0 when the sample is missed
+    float qlo;      // surrogate mode: |Q| - q, so that q + qlo carries |Q| in FP64
 };
 
 // Traces neutron i.  tab_size/tab_norm point to the LDS copies of the
@@ -1862,7 +1863,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
                                                const double* tab_size, const double* tab_norm,
                                                const float* lq, int part = 0, int nparts = 1)
 {
-    Event ev{-1, 0.0f, 0.0f};
+    Event ev{-1, 0.0f, 0.0f, 0.0f};
     const uint32_t ilo = (uint32_t)i, ihi = (uint32_t)(i >> 32);
     const U4 r0 = philox4x32_10(ilo, ihi, 0u, a.exp_id, a.seed_lo, a.seed_hi);
     const U4 r1 = philox4x32_10(ilo, ihi, 1u, a.exp_id, a.seed_lo, a.seed_hi);
@@ -1876,6 +1877,7 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     const double qd = geo.qd;
     const float q = (float)qd;
     ev.q = in_sample ? q : 0.0f;
+    if constexpr (MODE == 2) ev.qlo = in_sample ? (float)(qd - (double)q) : 0.0f;
 
     // attenuation along the path inside the slab, before the scattering point
     // and after it along k_f to the face where it leaves (when asked for)

@@ -271,6 +271,12 @@ struct SurConst {
     float mid0, scale0;   // normalisation of ln(q s0): (x - mid0) * scale0
     float f2_0;           // <F^2>(0)
     float kref;           // Rg^2 / 6 (A^2): P_ref = (1 + q^2 kref)^-2
+    // the in-domain judge: bins of ln(q s0) (FP64, from |Q| in FP64) over
+    // [jlo, jlo + nbins / jinv); flags[b] sends bin b's neutrons to the exact
+    // pass; nbins = 0: no judge
+    double ls0d, jlo, jinv;
+    int32_t jnb;
+    const unsigned char* flags;
 };
 
 // Surrogate tracer.  Geometry and S(q) per lane; the network per wave (16
@@ -290,10 +296,16 @@ __global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const m
     for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < a.n; j0 += stride) {
         const uint64_t j = j0 + threadIdx.x;
         const bool valid = j < a.n;
-        Event ev{-1, 0.0f, 0.0f};
+        Event ev{-1, 0.0f, 0.0f, 0.0f};
         if (valid) ev = trace_neutron<KIND, 2>(loop_args(kernel_args()), a.first + j, nullptr, nullptr, nullptr);
         const float x0 = __logf(ev.q) + sc.ls0;
-        const bool in_dom = valid && ev.pixel >= 0 && x0 >= sc.lo0 && x0 <= sc.hi0;
+        // the domain and the judge's bin from ln(q s0) in FP64
+        const double x0d = valid && ev.q > 0.0f ? log((double)ev.q + (double)ev.qlo) + sc.ls0d : -1e300;
+        bool in_dom = valid && ev.pixel >= 0 && x0d >= (double)sc.lo0 && x0d <= (double)sc.hi0;
+        if (in_dom && sc.jnb > 0) {
+            const int b = (int)fmin(fmax(floor((x0d - sc.jlo) * sc.jinv), 0.0), (double)(sc.jnb - 1));
+            in_dom = sc.flags[b] == 0;
+        }
         float* xr = xs + lane * mlp::kIn;
         xr[0] = (fminf(fmaxf(x0, sc.lo0), sc.hi0) - sc.mid0) * sc.scale0;
         xr[1] = sc.x1;

@@ -31,6 +31,9 @@ using namespace sans;
 namespace {
 
 constexpr size_t kLdsMax = 160 * 1024;
+// the surrogate's default in-domain judge: tolerance on ln <F^2>, bins of ln(q s0)
+constexpr double kSurJudgeTol = 1e-3;
+constexpr int kSurJudgeBins = 2048;
 
 thread_local std::string g_last_error;
 
@@ -349,6 +352,11 @@ struct sans_model_s {
     unsigned long long* d_queue = nullptr;
     size_t queue_cap = 0;
     unsigned* d_qcount = nullptr;
+    // the surrogate's in-domain judge: flags per bin of ln(q s0) (device), the
+    // bin count (0 = none) and the tolerance it was run with
+    unsigned char* d_sur_flags = nullptr;
+    int sur_nbins = 0;
+    double sur_tol = 0.0;
     int device = 0;
     int num_cu = 256;
 };
@@ -1471,6 +1479,11 @@ bool surrogate_inputs(const sans_model_s* m, SurConst& sc)
     const int kind = p.kind == SANS_PARALLELEPIPED ? kParallelepiped : kEllipsoid;
     sc.kref = (float)((p.size[0] * p.size[0] + p.size[1] * p.size[1] + p.size[2] * p.size[2])
                       * sur_rg2_scale(kind) / 6.0);
+    sc.ls0d = std::log(p.size[0]);
+    sc.jlo = (double)m->sur_lo[0];
+    sc.jinv = m->sur_hi[0] > m->sur_lo[0] ? m->sur_nbins / ((double)m->sur_hi[0] - (double)m->sur_lo[0]) : 0.0;
+    sc.jnb = m->sur_hi[0] > m->sur_lo[0] ? m->sur_nbins : 0;
+    sc.flags = m->d_sur_flags;
     return true;
 }
 
@@ -1498,6 +1511,76 @@ int run_surrogate(sans_model_s* m, const TraceArgs& a, const SurConst& sc, doubl
                            ac, lay, m->d_queue, m->d_qcount, det);
         HIP_TRY(hipGetLastError());
     }
+    return SANS_OK;
+}
+
+// The in-domain judge of the attached network on this model's line of inputs
+// (its size ratios and width fixed, x0 = ln(q s0) over the box): the
+// network's output against the exact average's target at the edges and
+// midpoints of nbins bins; a bin whose error exceeds tol at any of its three
+// points is flagged.  err (host, [2 nbins + 1]) and flags (host, [nbins]) are
+// optional copies of the result.
+int judge_surrogate(sans_model_s* m, double tol, int nbins, float* err, unsigned char* flags)
+{
+    const sans_params& p = m->p;
+    SurConst sc;
+    std::memset(&sc, 0, sizeof(sc));
+    m->sur_nbins = 0;
+    if (!surrogate_inputs(m, sc)) return SANS_OK;   // the whole model takes the exact path
+    const int npt = 2 * nbins + 1;
+    const double lo = m->sur_lo[0], hi = m->sur_hi[0];
+    std::vector<float> x((size_t)npt * mlp::kIn, 0.0f), u((size_t)npt * mlp::kIn, 0.0f);
+    for (int j = 0; j < npt; ++j) {
+        const double x0 = lo + (hi - lo) * j / (2.0 * nbins);
+        float* xr = &x[(size_t)j * mlp::kIn];
+        float* ur = &u[(size_t)j * mlp::kIn];
+        xr[0] = (float)x0;
+        xr[1] = (float)std::log(p.size[1] / p.size[0]);
+        xr[2] = (float)std::log(p.size[2] / p.size[0]);
+        xr[3] = (float)p.poly;
+        ur[0] = hi > lo ? (float)((2.0 * x0 - lo - hi) / (hi - lo)) : 0.0f;
+        ur[1] = sc.x1;
+        ur[2] = sc.x2;
+        ur[3] = sc.x3;
+    }
+    float *d_x = nullptr, *d_u = nullptr, *d_t = nullptr, *d_y = nullptr, *d_ws = nullptr;
+    const size_t wsb = sans_mlp_workspace_bytes(npt);
+    hipError_t e = hipMalloc(&d_x, sizeof(float) * x.size());
+    if (e == hipSuccess) e = hipMalloc(&d_u, sizeof(float) * u.size());
+    if (e == hipSuccess) e = hipMalloc(&d_t, sizeof(float) * npt);
+    if (e == hipSuccess) e = hipMalloc(&d_y, sizeof(float) * npt);
+    if (e == hipSuccess) e = hipMalloc(&d_ws, wsb);
+    if (e == hipSuccess) e = hipMemcpy(d_x, x.data(), sizeof(float) * x.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_u, u.data(), sizeof(float) * u.size(), hipMemcpyHostToDevice);
+    int rc = SANS_OK;
+    std::vector<float> t(npt), y(npt);
+    if (e == hipSuccess) {
+        rc = sans_pq_dataset(p.kind, d_x, npt, d_t, p.quad_n, nullptr);
+        if (rc == SANS_OK && sans_mlp_forward(m->d_sur_w, d_u, npt, d_y, d_ws, nullptr) != 0)
+            rc = fail(SANS_E_HIP, "judge: network forward failed");
+        if (rc == SANS_OK) e = hipStreamSynchronize(nullptr);
+        if (rc == SANS_OK && e == hipSuccess) e = hipMemcpy(t.data(), d_t, sizeof(float) * npt, hipMemcpyDeviceToHost);
+        if (rc == SANS_OK && e == hipSuccess) e = hipMemcpy(y.data(), d_y, sizeof(float) * npt, hipMemcpyDeviceToHost);
+    }
+    for (float* ptr : {d_x, d_u, d_t, d_y, d_ws})
+        if (ptr) (void)hipFree(ptr);
+    if (e != hipSuccess) return fail(SANS_E_HIP, std::string("judge: ") + hipGetErrorString(e));
+    if (rc) return rc;
+    std::vector<unsigned char> fl(nbins);
+    for (int b = 0; b < nbins; ++b) {
+        const double e0 = std::fabs((double)y[2 * b] - t[2 * b]), e1 = std::fabs((double)y[2 * b + 1] - t[2 * b + 1]),
+                     e2 = std::fabs((double)y[2 * b + 2] - t[2 * b + 2]);
+        fl[b] = e0 > tol || e1 > tol || e2 > tol;
+    }
+    if (err)
+        for (int j = 0; j < npt; ++j) err[j] = std::fabs(y[j] - t[j]);
+    if (flags) std::memcpy(flags, fl.data(), nbins);
+    if (m->d_sur_flags) HIP_TRY(hipFree(m->d_sur_flags));
+    m->d_sur_flags = nullptr;
+    HIP_TRY(hipMalloc(&m->d_sur_flags, nbins));
+    HIP_TRY(hipMemcpy(m->d_sur_flags, fl.data(), nbins, hipMemcpyHostToDevice));
+    m->sur_nbins = nbins;
+    m->sur_tol = tol;
     return SANS_OK;
 }
 
@@ -1598,6 +1681,7 @@ int sans_model_destroy(sans_model_t m)
     if (m->d_sur_pack) (void)hipFree(m->d_sur_pack);
     if (m->d_queue) (void)hipFree(m->d_queue);
     if (m->d_qcount) (void)hipFree(m->d_qcount);
+    if (m->d_sur_flags) (void)hipFree(m->d_sur_flags);
     delete m;
     return SANS_OK;
 }
@@ -1897,7 +1981,17 @@ int sans_model_attach_surrogate(sans_model_t m, const void* w_bf16, const float*
         m->sur_hi[k] = domain_hi[k];
     }
     m->sur_attached = true;
-    return SANS_OK;
+    // the default in-domain judge: 1e-3 on ln <F^2> over 2048 bins
+    return judge_surrogate(m, kSurJudgeTol, kSurJudgeBins, nullptr, nullptr);
+}
+
+int sans_model_judge_surrogate(sans_model_t m, double tol, int32_t nbins, float* err, uint8_t* flags)
+{
+    if (!m) return fail(SANS_E_INVALID_ARG, "model is NULL");
+    if (!m->sur_attached) return fail(SANS_E_UNSUPPORTED, "judge: no network attached");
+    if (nbins < 1 || nbins > 65536) return fail(SANS_E_INVALID_ARG, "judge: nbins must be in 1..65536");
+    if (!(tol >= 0.0)) return fail(SANS_E_INVALID_ARG, "judge: tol must be >= 0");
+    return judge_surrogate(m, tol, nbins, err, flags);
 }
 
 int sans_pq_dataset(int32_t kind, const float* x, int64_t n, float* out, int32_t quad_n, void* stream)

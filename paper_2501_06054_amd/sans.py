@@ -96,6 +96,8 @@ def _load():
     L.sans_batch_release.argtypes = []
     L.sans_model_attach_surrogate.argtypes = [vp, vp, P(C.c_float), P(C.c_float)]
     L.sans_model_attach_surrogate.restype = C.c_int
+    L.sans_model_judge_surrogate.argtypes = [vp, C.c_double, i32, P(C.c_float), P(C.c_uint8)]
+    L.sans_model_judge_surrogate.restype = C.c_int
     L.sans_pq_dataset.argtypes = [i32, vp, i64, vp, i32, vp]
     L.sans_pq_dataset.restype = C.c_int
     L.sans_mlp_param_count.restype = i64
@@ -336,6 +338,18 @@ def sans_model_attach_surrogate(h, w_bf16, lo, hi) -> None:
     hi4 = (C.c_float * 4)(*hi)
     _check(lib.sans_model_attach_surrogate(h, _dev(w_bf16, torch.bfloat16, "w_bf16"), lo4, hi4),
            "sans_model_attach_surrogate")
+
+
+def sans_model_judge_surrogate(h, tol: float, nbins: int):
+    """Runs the in-domain judge; returns (errors [2 nbins + 1], flags [nbins])
+    as NumPy arrays."""
+    import numpy as np
+    err = np.zeros(2 * nbins + 1, dtype=np.float32)
+    flags = np.zeros(nbins, dtype=np.uint8)
+    _check(lib.sans_model_judge_surrogate(h, float(tol), nbins, err.ctypes.data_as(C.POINTER(C.c_float)),
+                                          flags.ctypes.data_as(C.POINTER(C.c_uint8))),
+           "sans_model_judge_surrogate")
+    return err, flags
 
 
 def sans_abi_params_size() -> int:

@@ -231,12 +231,16 @@ def test_surrogate_tracer_matches_oracle(S, SG, model, box_hi0):
     p = wl["params"]
     sg = SG.Surrogate(model)
     sg.wb.copy_(wb)
+    lo, hi = list(sg.lo), list(sg.hi)
     if box_hi0 is not None:
-        lo, hi = list(sg.lo), list(sg.hi)
         hi[0] = box_hi0
-        sg.lo, sg.hi = tuple(lo), tuple(hi)
+    # the box as the device holds it (FP32), on both sides
+    sg.lo, sg.hi = tuple(float(np.float32(v)) for v in lo), tuple(float(np.float32(v)) for v in hi)
     m = S.Model(p)
     sg.attach(m.handle)
+    # the plumbing of the network itself: no neutron sent to the exact pass by
+    # the judge (the oracle's surrogate mode starts without one)
+    S.sans_model_judge_surrogate(m.handle, math.inf, 64)
     n, seed = 20011, 13
     det = m.trace(n, seed)
     torch.cuda.synchronize()
@@ -261,6 +265,69 @@ def test_surrogate_tracer_matches_oracle(S, SG, model, box_hi0):
     nz = ref != 0
     pix = float(np.max(np.abs(d[nz] - ref[nz]) / np.abs(ref[nz])))
     print("SURROGATE_TRACER_VS_ORACLE", dict(model=model, bar=bar, pixel=pix, total=tot))
+    assert tot <= bar and pix <= bar, (bar, pix, tot)
+    m.close()
+
+
+@pytest.mark.parametrize("model", ["parallelepiped", "spheroid"])
+def test_judge_matches_oracle(S, SG, model):
+    """The in-domain judge: its errors at the bins' points against the
+    oracle's (network against the exact average, both sides' own), within the
+    forward bar plus the training targets' bar; then, at a tolerance placed in
+    a gap of the oracle's errors wider than that margin on both sides, the
+    same flags, and the judged tracer against the oracle's judged surrogate
+    mode (flagged bins traced exactly) within the surrogate tracer's bar."""
+    wb, w64 = bf16_weights(SG, 9, scale=0.3, bias=0.2)
+    wl = W.workload("surrogate_" + model)
+    p = wl["params"]
+    sg = SG.Surrogate(model)
+    sg.wb.copy_(wb)
+    sg.lo = tuple(float(np.float32(v)) for v in sg.lo)
+    sg.hi = tuple(float(np.float32(v)) for v in sg.hi)
+    m = S.Model(p)
+    sg.attach(m.handle)
+    nb = 64
+    err_dev, _ = S.sans_model_judge_surrogate(m.handle, math.inf, nb)
+    oracle.set_surrogate(w64, sg.lo, sg.hi)
+    _, err_orc = oracle.surrogate_judge(p, math.inf, nb)
+    # forward bar over the model's line of inputs, plus the targets' bar
+    lo, hi = W.SURROGATE_BOX[model]
+    x0 = np.linspace(-1.0, 1.0, 2 * nb + 1)
+    u = np.zeros((x0.size, 8))
+    u[:, 0] = x0
+    xs = (0.0, math.log(p["size"][1] / p["size"][0]), math.log(p["size"][2] / p["size"][0]), p["poly"])
+    for k in (1, 2, 3):
+        u[:, k] = 0.0 if hi[k] == lo[k] else (2 * xs[k] - lo[k] - hi[k]) / (hi[k] - lo[k])
+    _, _, h = oracle.mlp_forward(w64, u, round_bf16=True, hidden=True)
+    _, _, w4, b4 = _layers(w64)
+    margin = 2.0**-9 * (np.abs(h[3]) @ np.abs(w4) + abs(b4)) + 2e-4 + 1e-5 * err_orc
+    gap = np.abs(err_dev - err_orc) - margin
+    print("JUDGE_ERRORS", dict(model=model, worst_fraction_of_margin=float(np.max(np.abs(err_dev - err_orc) / margin))))
+    assert np.all(gap <= 0.0), float(np.max(gap))
+    # a tolerance in the middle of the widest gap between the oracle's errors
+    # away from every point by more than the margin
+    es = np.sort(err_orc)
+    mg = float(np.max(margin))
+    gaps = [(es[i + 1] - es[i], 0.5 * (es[i] + es[i + 1])) for i in range(es.size - 1)
+            if es[i + 1] - es[i] > 2.5 * mg and 0 < i < es.size - 2]
+    assert gaps, "no gap in the judge's errors wide enough to place a tolerance"
+    tol = max(gaps)[1]
+    _, f_dev = S.sans_model_judge_surrogate(m.handle, tol, nb)
+    k_orc, _ = oracle.surrogate_judge(p, tol, nb)
+    f_orc = np.array([max(err_orc[2 * b], err_orc[2 * b + 1], err_orc[2 * b + 2]) > tol for b in range(nb)])
+    assert int(f_orc.sum()) == k_orc and 0 < k_orc < nb
+    assert np.array_equal(f_dev.astype(bool), f_orc)
+    n, seed = 20011, 17
+    det = m.trace(n, seed)
+    torch.cuda.synchronize()
+    ref = oracle.trace(p, n, seed, nthreads=NTHREADS)
+    d = det.cpu().numpy()
+    bar = math.expm1(2.0**-9 * float(np.max(np.abs(h[3]) @ np.abs(w4) + abs(b4))))
+    assert np.array_equal(d != 0, ref != 0)
+    tot = abs(d.sum() - ref.sum()) / abs(ref.sum())
+    nz = ref != 0
+    pix = float(np.max(np.abs(d[nz] - ref[nz]) / np.abs(ref[nz])))
+    print("JUDGED_TRACER_VS_ORACLE", dict(model=model, tol=tol, flagged=k_orc, bar=bar, pixel=pix, total=tot))
     assert tot <= bar and pix <= bar, (bar, pix, tot)
     m.close()
 
