@@ -2043,6 +2043,22 @@ int sans_pq_dataset(int32_t kind, const float* x, int64_t n, float* out, int32_t
 // ------------------------------------------------------------------ batch host side
 namespace {
 
+// A schedule of the batched launch: the tile (neutrons per tile, or cost
+// units per tile), how the experiments are split into tiles, and how many
+// persistent workgroups share a compute unit.
+//   split 0: tiles of `tile` neutrons (an experiment's remainder last), whole
+//            tiles in experiment order, then the remainders largest first;
+//   split 1: tiles of tile / cost(e) neutrons for the per-neutron cost of
+//            experiment e's model, all tiles ordered by their cost, largest
+//            first (longest-processing-time order);
+//   occ:     persistent workgroups per compute unit (as many as the LDS
+//            histogram lets reside together).
+struct BatchSchedule {
+    long tile = 1l << 18;
+    int split = 0;
+    int occ = 1;
+};
+
 struct BatchCache {
     std::mutex mu;
     TraceArgs* d_exps = nullptr;
@@ -2062,7 +2078,7 @@ struct BatchCache {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::string graph_key;
-    std::map<std::string, long> tuned;  // key -> tile size (this process)
+    std::map<std::string, BatchSchedule> tuned;  // key -> schedule (this process)
 
     void release()
     {
@@ -2098,8 +2114,29 @@ BatchCache& batch_cache()
     return c;
 }
 
-constexpr long kDefaultTile = 1l << 18;
 const long kTileCandidates[] = {1l << 16, 1l << 17, 1l << 18, 1l << 19, 1l << 20};
+
+// Relative per-neutron cost of an experiment's model (1 for the closed-form
+// amplitudes; models that integrate per event scale with their rule):
+// issue-slot counts of the per-neutron steps, about 900 for a plain
+// anisotropic particle, 40-60 per node of an inner rule.
+double model_cost(const sans_params& p)
+{
+    const double n = p.quad_n;
+    switch (p.kind) {
+    case SANS_BARBELL:
+    case SANS_CAPPED_CYLINDER: return 1.0 + 43.0 * n / 900.0;
+    case SANS_SUPERBALL: return 1.0 + (19.0 * n + 38.0 * n * n) / 900.0;
+    case SANS_PRINGLE: return 1.0 + 36.0 * 2.0 * n * n / 900.0;
+    case SANS_PEARL_NECKLACE: return 1.0 + (55.0 * n + 8.0 * p.extra[0]) / 900.0;
+    case SANS_LAMELLAR_STACK_CAILLE:
+    case SANS_LAMELLAR_HG_STACK_CAILLE:
+    case SANS_LAMELLAR_STACK_PARACRYSTAL: return 1.0 + 36.0 * p.extra[0] / 900.0;
+    case SANS_BINARY_HARD_SPHERE: return 2.1;
+    case SANS_POLYMER_EXCL_VOLUME: return 1.6;
+    default: return is_shape_independent(p.kind) ? 0.75 : (is_aniso(p.kind) ? 1.1 : 1.0);
+    }
+}
 
 std::string tune_key(int n_exp, double total_n, int nx, int ny, int num_cu)
 {
@@ -2110,10 +2147,11 @@ std::string tune_key(int n_exp, double total_n, int nx, int ny, int num_cu)
 }
 
 // Tuning cache file: one JSON object, one entry per line:
-//   "key": {"tile": T, "ms": t},
-std::map<std::string, long> read_tune_cache(const char* path)
+//   "key": {"tile": T, "split": s, "occ": o, "ms": t},
+// (an entry without "split" or "occ" takes 0 and 1).
+std::map<std::string, BatchSchedule> read_tune_cache(const char* path)
 {
-    std::map<std::string, long> out;
+    std::map<std::string, BatchSchedule> out;
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
@@ -2121,42 +2159,67 @@ std::map<std::string, long> read_tune_cache(const char* path)
         const size_t q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
         const size_t t = line.find("\"tile\":");
         if (q0 == std::string::npos || q1 == std::string::npos || t == std::string::npos) continue;
-        out[line.substr(q0 + 1, q1 - q0 - 1)] = std::atol(line.c_str() + t + 7);
+        BatchSchedule sc;
+        sc.tile = std::atol(line.c_str() + t + 7);
+        const size_t sp = line.find("\"split\":"), oc = line.find("\"occ\":");
+        if (sp != std::string::npos) sc.split = std::atoi(line.c_str() + sp + 8);
+        if (oc != std::string::npos) sc.occ = std::atoi(line.c_str() + oc + 6);
+        if (sc.tile < 1024 || sc.split < 0 || sc.split > 1 || sc.occ < 1 || sc.occ > 8) continue;
+        out[line.substr(q0 + 1, q1 - q0 - 1)] = sc;
     }
     return out;
 }
 
-void write_tune_cache(const char* path, const std::map<std::string, long>& tiles,
+void write_tune_cache(const char* path, const std::map<std::string, BatchSchedule>& sched,
                       const std::map<std::string, double>& ms)
 {
     std::ofstream f(path, std::ios::trunc);
     f << "{\n";
     size_t i = 0;
-    for (const auto& kv : tiles) {
+    for (const auto& kv : sched) {
         const auto it = ms.find(kv.first);
-        f << "\"" << kv.first << "\": {\"tile\": " << kv.second << ", \"ms\": "
-          << (it == ms.end() ? 0.0 : it->second) << "}" << (++i < tiles.size() ? "," : "") << "\n";
+        f << "\"" << kv.first << "\": {\"tile\": " << kv.second.tile << ", \"split\": " << kv.second.split
+          << ", \"occ\": " << kv.second.occ << ", \"ms\": " << (it == ms.end() ? 0.0 : it->second) << "}"
+          << (++i < sched.size() ? "," : "") << "\n";
     }
     f << "}\n";
 }
 
-// Queues the batch on stream s with tile size T (graph captured once per shape).
+// Queues the batch on stream s with schedule sc (graph captured once per
+// shape and schedule).  cost: per-neutron cost of each experiment's model.
 int run_batch(BatchCache& c, int n_exp, const std::vector<TraceArgs>& exps,
-              const std::vector<SchulzJob>& jobs, const uint64_t* n_neutrons, long T, int npix, int M,
-              double* dets, size_t lds, int num_cu, hipStream_t s)
+              const std::vector<SchulzJob>& jobs, const uint64_t* n_neutrons, const std::vector<double>& cost,
+              const BatchSchedule& sc, int npix, int M, double* dets, size_t lds, int num_cu, hipStream_t s)
 {
-    // tiles: whole tiles first, then the remainders, each group by decreasing size
     std::vector<BatchTile> tiles;
-    std::vector<BatchTile> rest;
-    for (int e = 0; e < n_exp; ++e) {
-        uint64_t f = 0;
-        const uint64_t n = n_neutrons[e];
-        for (; f + (uint64_t)T <= n; f += T) tiles.push_back(BatchTile{(unsigned)e, (unsigned)T, f});
-        if (f < n) rest.push_back(BatchTile{(unsigned)e, (unsigned)(n - f), f});
+    if (sc.split == 0) {
+        // whole tiles first, then the remainders, by decreasing size
+        std::vector<BatchTile> rest;
+        const uint64_t T = (uint64_t)sc.tile;
+        for (int e = 0; e < n_exp; ++e) {
+            uint64_t f = 0;
+            const uint64_t n = n_neutrons[e];
+            for (; f + T <= n; f += T) tiles.push_back(BatchTile{(unsigned)e, (unsigned)T, f});
+            if (f < n) rest.push_back(BatchTile{(unsigned)e, (unsigned)(n - f), f});
+        }
+        std::stable_sort(rest.begin(), rest.end(),
+                         [](const BatchTile& x, const BatchTile& y) { return x.count > y.count; });
+        tiles.insert(tiles.end(), rest.begin(), rest.end());
+    } else {
+        // equal-cost tiles, all of them in decreasing order of cost
+        std::vector<std::pair<double, BatchTile>> tc;
+        for (int e = 0; e < n_exp; ++e) {
+            const uint64_t T = (uint64_t)std::max(1024.0, std::min(4.0e9, (double)sc.tile / cost[e]));
+            const uint64_t n = n_neutrons[e];
+            for (uint64_t f = 0; f < n; f += T) {
+                const uint64_t cnt = std::min(T, n - f);
+                tc.push_back({cost[e] * (double)cnt, BatchTile{(unsigned)e, (unsigned)cnt, f}});
+            }
+        }
+        std::stable_sort(tc.begin(), tc.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+        tiles.reserve(tc.size());
+        for (const auto& t : tc) tiles.push_back(t.second);
     }
-    std::stable_sort(rest.begin(), rest.end(),
-                     [](const BatchTile& x, const BatchTile& y) { return x.count > y.count; });
-    tiles.insert(tiles.end(), rest.begin(), rest.end());
     const int ntiles = (int)tiles.size();
     int rc;
     if ((rc = ensure(c.d_tiles, c.tiles_cap, std::max<size_t>(1, tiles.size())))) return rc;
@@ -2170,7 +2233,7 @@ int run_batch(BatchCache& c, int n_exp, const std::vector<TraceArgs>& exps,
 
     std::ostringstream key;
     key << n_exp << "/" << ntiles << "/" << jobs.size() << "/" << npix << "/" << M << "/" << dets << "/"
-        << c.d_exps << "/" << c.d_tiles << "/" << c.d_jobs << "/" << c.d_tables;
+        << c.d_exps << "/" << c.d_tiles << "/" << c.d_jobs << "/" << c.d_tables << "/" << sc.occ;
     if (c.graph_key != key.str()) {
         if (c.exec) (void)hipGraphExecDestroy(c.exec);
         if (c.graph) (void)hipGraphDestroy(c.graph);
@@ -2185,7 +2248,7 @@ int run_batch(BatchCache& c, int n_exp, const std::vector<TraceArgs>& exps,
             hipLaunchKernelGGL(k_schulz_tables, dim3((unsigned)jobs.size()), dim3(kSchulzBlock), 0,
                                c.cap_stream, c.d_jobs, M, c.d_tables, gl16_nodes());
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, c.cap_stream, c.d_counter, 1);
-        const unsigned grid = (unsigned)std::max(1, std::min(ntiles, num_cu));
+        const unsigned grid = (unsigned)std::max(1, std::min(ntiles, num_cu * sc.occ));
         hipLaunchKernelGGL(batch_kernel(), dim3(grid), dim3(kHistBlock), lds, c.cap_stream, c.d_exps, c.d_tiles,
                            ntiles, c.d_counter, dets, npix, M);
         hipError_t le = hipGetLastError();
@@ -2299,44 +2362,77 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
                                hipMemcpyHostToDevice, s));
     if ((rc = set_lds_limit((const void*)batch_kernel(), lds))) return rc;
 
-    // tile size: tuning cache, else autotune (when a cache path is given), else default
+    // schedule: tuning cache, else autotune (when a cache path is given), else default
+    std::vector<double> cost(n_exp);
+    for (int e = 0; e < n_exp; ++e) cost[e] = model_cost(p[e]);
+    // persistent workgroups that can share a compute unit (LDS histogram)
+    const int max_occ = (int)std::max<size_t>(1, std::min<size_t>(4, kLdsMax / (lds + 64)));
     const std::string key = tune_key(n_exp, total_n, nx, ny, num_cu);
-    long T = kDefaultTile;
-    std::map<std::string, long> file_tiles;
-    if (tune_cache) file_tiles = read_tune_cache(tune_cache);
-    if (tune_cache && file_tiles.count(key)) {
-        T = file_tiles[key];
+    BatchSchedule sched;
+    std::map<std::string, BatchSchedule> file_sched;
+    if (tune_cache) file_sched = read_tune_cache(tune_cache);
+    if (tune_cache && file_sched.count(key)) {
+        sched = file_sched[key];
+        sched.occ = std::min(sched.occ, max_occ);
     } else if (c.tuned.count(key)) {
-        T = c.tuned[key];
+        sched = c.tuned[key];
     } else if (tune_cache) {
+        // coordinate search: the tile size under the plain split, then the
+        // cost-weighted split at the best tile and its neighbours, then the
+        // occupancy; each candidate runs the whole batch twice (warm, timed)
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         double best = 1e300;
-        for (long cand : kTileCandidates) {
-            if ((rc = run_batch(c, n_exp, exps, jobs, n_neutrons, cand, npix, M, detectors_out, lds, num_cu, s)))
-                return rc;
+        auto time_it = [&](const BatchSchedule& cand, double* ms_out) -> int {
+            int r;
+            if ((r = run_batch(c, n_exp, exps, jobs, n_neutrons, cost, cand, npix, M, detectors_out, lds, num_cu, s)))
+                return r;
             HIP_TRY(hipEventRecord(e0, s));
-            if ((rc = run_batch(c, n_exp, exps, jobs, n_neutrons, cand, npix, M, detectors_out, lds, num_cu, s)))
-                return rc;
+            if ((r = run_batch(c, n_exp, exps, jobs, n_neutrons, cost, cand, npix, M, detectors_out, lds, num_cu, s)))
+                return r;
             HIP_TRY(hipEventRecord(e1, s));
             HIP_TRY(hipEventSynchronize(e1));
             float ms = 0.0f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
+            *ms_out = ms;
+            return SANS_OK;
+        };
+        auto consider = [&](const BatchSchedule& cand) -> int {
+            double ms = 0.0;
+            const int r = time_it(cand, &ms);
+            if (r == SANS_OK && ms < best) {
                 best = ms;
-                T = cand;
+                sched = cand;
             }
+            return r;
+        };
+        for (long t : kTileCandidates) {
+            BatchSchedule cand;
+            cand.tile = t;
+            if ((rc = consider(cand))) return rc;
+        }
+        const long t0 = sched.tile;
+        for (long t : {t0 / 2, t0, t0 * 2}) {
+            BatchSchedule cand;
+            cand.tile = t;
+            cand.split = 1;
+            if ((rc = consider(cand))) return rc;
+        }
+        for (int o = 2; o <= max_occ; o *= 2) {
+            BatchSchedule cand = sched;
+            cand.occ = o;
+            if ((rc = consider(cand))) return rc;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        file_tiles[key] = T;
+        file_sched[key] = sched;
         std::map<std::string, double> ms;
         ms[key] = best;
-        write_tune_cache(tune_cache, file_tiles, ms);
+        write_tune_cache(tune_cache, file_sched, ms);
     }
-    c.tuned[key] = T;
-    return run_batch(c, n_exp, exps, jobs, n_neutrons, T, npix, M, detectors_out, lds, num_cu, s);
+    c.tuned[key] = sched;
+    return run_batch(c, n_exp, exps, jobs, n_neutrons, cost, sched, npix, M, detectors_out, lds, num_cu, s);
 }
 
 int sans_batch_release(void)

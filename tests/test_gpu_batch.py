@@ -115,9 +115,40 @@ def test_batch_tuning_cache(S, tmp_path):
     entries = json.load(open(path))
     assert len(entries) == 1
     (entry,) = entries.values()
-    assert entry["tile"] in (1 << 16, 1 << 17, 1 << 18, 1 << 19, 1 << 20)
+    # the tile searched over 2^16 .. 2^20 (and halved or doubled for the
+    # cost-weighted split), the split and the workgroups per compute unit
+    assert entry["tile"] in [1 << k for k in range(15, 22)]
+    assert entry["split"] in (0, 1)
+    assert entry["occ"] == 1          # a 128 x 128 histogram leaves room for one workgroup per CU
     b = _run_batch(S, exps, tune_cache=path)   # read back
     assert np.allclose(a, b, rtol=SAME_EXPERIMENT_RTOL, atol=0)
+
+
+@pytest.mark.parametrize("tile,split,occ", [(1 << 16, 0, 1), (1 << 15, 1, 1), (1 << 17, 1, 2), (1 << 16, 0, 4)])
+def test_batch_schedules_give_the_same_detectors(S, tmp_path, tile, split, occ):
+    """Any schedule read from the tuning cache (tile size, split, workgroups
+    per CU) traces the same experiments: every detector equals its plain
+    trace.  64 x 64 detectors, whose LDS histogram lets four workgroups share
+    a compute unit."""
+    exps = W.batch_experiments(n_exp=24, seed=4096, nx=64, n_lo=2e4, n_hi=3e5)
+    total = float(sum(x["n"] for x in exps))
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    key = f"E{len(exps)}_S{int(round(np.log2(total)))}_D64x64_CU{cu}"
+    path = str(tmp_path / "tune.json")
+    with open(path, "w") as f:
+        json.dump({key: {"tile": tile, "split": split, "occ": occ, "ms": 0.0}}, f)
+    out = torch.empty((len(exps), 64, 64), dtype=torch.float64, device="cuda")
+    S.sans_trace_batch([x["params"] for x in exps], [x["n"] for x in exps], [x["seed"] for x in exps], out,
+                       tune_cache=path)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert json.load(open(path))[key]["split"] == split       # read, not re-tuned
+    for e, x in enumerate(exps):
+        m = S.Model(x["params"])
+        ref = m.trace(x["n"], x["seed"], exp_id=e).cpu().numpy()
+        m.close()
+        assert np.array_equal(got[e] != 0, ref != 0), e
+        assert np.allclose(got[e], ref, rtol=SAME_EXPERIMENT_RTOL, atol=0), e
 
 
 def test_batch_rejects_mismatched_detectors(S):
