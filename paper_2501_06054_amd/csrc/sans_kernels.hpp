@@ -234,9 +234,10 @@ __global__ __launch_bounds__(kBlock) void k_pq_avg(const TraceArgs a, LdsLayout 
 
 // ------------------------------------------------------------------ batched experiments
 // Persistent kernel over a queue of tiles (experiment e, neutron range).
-// Each workgroup pops a tile, stages that experiment's Schulz table into LDS,
-// traces the tile into an LDS histogram of the experiment's detector and
-// adds the histogram to the detector.  The model is uniform per tile, so the
+// Each workgroup pops a tile, traces it into an LDS histogram of the
+// experiment's detector (the experiment's size table is read from global
+// memory, through the caches: the histogram takes the LDS) and adds the
+// histogram to the detector.  The model is uniform per tile, so the
 // switch on it is a scalar branch; every workgroup leaves the loop when the
 // queue is exhausted.
 struct BatchTile {
