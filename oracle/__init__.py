@@ -36,7 +36,8 @@ KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelep
         "lamellar_hg": 52, "lamellar_stack_caille": 53, "lamellar_hg_stack_caille": 54,
         "lamellar_stack_paracrystal": 55, "core_shell_bicelle_elliptical_belt_rough": 56,
         "raspberry": 57, "pearl_necklace": 58, "binary_hard_sphere": 59, "adsorbed_layer": 60,
-        "pringle": 61}
+        "pringle": 61,
+        "flexible_cylinder_elliptical": 62}
 SQ_KIND = {"hard_sphere": 0, "sticky_hard_sphere": 1, "square_well": 2}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
@@ -133,6 +134,10 @@ def lib():
             getattr(L, f).restype = d
         L.orc_py_sq.argtypes = [d, d, d]
         L.orc_py_sq.restype = d
+        L.orc_flexcyl_chain.argtypes = [d, d, d, i32]
+        L.orc_flexcyl_chain.restype = d
+        L.orc_flexcyl_section.argtypes = [d, d, d, i32]
+        L.orc_flexcyl_section.restype = d
         L.orc_sticky_lambda.argtypes = [d, d]
         L.orc_sticky_lambda.restype = d
         L.orc_sticky_sq.argtypes = [d, d, d, d]
@@ -457,3 +462,13 @@ def surrogate_judge(p: dict, tol: float, nbins: int):
     if k < 0:
         raise ValueError("surrogate judge: no network set or bad arguments")
     return int(k), err
+
+
+def flexcyl_chain(q: float, L: float, b: float, n: int) -> float:
+    """Kholodenko's wormlike-chain factor of the flexible cylinder (n-point rule)."""
+    return lib().orc_flexcyl_chain(q, L, b, n)
+
+
+def flexcyl_section(q: float, R: float, eps: float, n: int) -> float:
+    """The elliptical cross-section factor averaged over its in-plane angle."""
+    return lib().orc_flexcyl_section(q, R, eps, n)

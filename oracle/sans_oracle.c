@@ -1213,6 +1213,77 @@ static double pringle_f2(const orc_params* p, const double s[3], double qa, doub
     return pre * pre * (re * re + im * im);
 }
 
+/* Flexible cylinder with an elliptical cross-section (kind 62; named in
+ * Table II of the paper, no formula given there).  The reading: a
+ * semiflexible (wormlike) chain of contour length L = size[1] and Kuhn
+ * length b = extra[0] whose local cross-section is an ellipse of semi-axes
+ * R = size[0] and eps R (eps = extra[1]), uniform contrast drho; the chain
+ * and the cross-section decouple,
+ *   F^2 = (drho pi eps R^2 L)^2 P_chain(q) P_cs(q),
+ * P_chain by Kholodenko's closed form for the wormlike chain (Macromolecules
+ * 26, 4179 (1993)): with x = 3L/b,
+ *   P_chain = (2/x) (I_1 - I_2/x),  I_n = int_0^x f(z) z^(n-1) dz,
+ *   f(z) = sinh(E z)/(E sinh z), E = sqrt(1 - (q b/3)^2) for q b < 3, and
+ *   f(z) = sin(F z)/(F sinh z), F = sqrt((q b/3)^2 - 1) above;
+ * the integrals by n-point Gauss-Legendre on [0, x_e], x_e = min(x, 40/(1 -
+ * E)) or min(x, 40) (the integrands fall as exp(-(1 - E) z) and exp(-z);
+ * what is cut is below e^-40), with f written as exp((E - 1) z) (1 -
+ * e^(-2Ez))/(E (1 - e^(-2z))) so that nothing overflows; P_cs the average of
+ * [2 J1(q r)/(q r)]^2 over the angle psi in [0, pi/2] between q and the
+ * ellipse's axes, r = R sqrt(sin^2 psi + eps^2 cos^2 psi), by the same
+ * n-point rule; n = quad_n in every mode. */
+static double flexcyl_chain(double q, double L, double b, int n)
+{
+    double gx[ORC_MAX_QUAD], gw[ORC_MAX_QUAD];
+    orc_gauss_legendre(n, gx, gw);
+    const double x = 3.0 * L / b, v = q * b / 3.0;
+    const int below = v < 1.0;
+    const double E = below ? sqrt(1.0 - v * v) : 0.0, F = below ? 0.0 : sqrt(v * v - 1.0);
+    double xe = x;
+    if (below && 1.0 - E > 0.0 && 40.0 / (1.0 - E) < xe) xe = 40.0 / (1.0 - E);
+    if (!below && xe > 40.0) xe = 40.0;
+    double i1 = 0.0, i2 = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double z = 0.5 * xe * (gx[k] + 1.0), wz = 0.5 * xe * gw[k];
+        double f;
+        if (below) {
+            /* sinh(Ez)/(E sinh z) */
+            const double num = E > 0.0 ? -expm1(-2.0 * E * z) / E : 2.0 * z;
+            f = exp((E - 1.0) * z) * num / (-expm1(-2.0 * z));
+        } else {
+            /* sin(Fz)/F -> z at q b = 3 */
+            f = 2.0 * (F > 0.0 ? sin(F * z) / F : z) * exp(-z) / (-expm1(-2.0 * z));
+        }
+        i1 += wz * f;
+        i2 += wz * f * z;
+    }
+    return 2.0 / x * (i1 - i2 / x);
+}
+
+static double flexcyl_section(double q, double R, double eps, int n)
+{
+    double gx[ORC_MAX_QUAD], gw[ORC_MAX_QUAD];
+    orc_gauss_legendre(n, gx, gw);
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const double psi = 0.25 * ORC_PI * (gx[k] + 1.0);
+        const double r = R * sqrt(sin(psi) * sin(psi) + eps * eps * cos(psi) * cos(psi));
+        const double l = orc_lambda1(q * r);
+        s += 0.5 * gw[k] * l * l;   /* (pi/4) w / (pi/2) */
+    }
+    return s;
+}
+
+double orc_flexcyl_chain(double q, double L, double b, int32_t n) { return flexcyl_chain(q, L, b, n); }
+double orc_flexcyl_section(double q, double R, double eps, int32_t n) { return flexcyl_section(q, R, eps, n); }
+
+static double flexcyl_f2(const orc_params* p, const double s[3], double q)
+{
+    const double R = s[0], L = s[1], b = p->extra[0], eps = p->extra[1];
+    const double v = (p->sld[0] - p->sld[2]) * ORC_PI * eps * R * R * L;
+    return v * v * flexcyl_chain(q, L, b, p->quad_n) * flexcyl_section(q, R, eps, p->quad_n);
+}
+
 /* The squared amplitude of one particle, or for the micelle its scattering
  * per particle (it has incoherent chain terms); for the shape-independent
  * models their cross-section in 1/cm. */
@@ -1222,6 +1293,7 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
     if (lamellar(p->kind)) return lamellar_iq(p, s, q);
     if (p->kind == 59) return binary_hs_f2(p, s, q);
     if (p->kind == 61) return pringle_f2(p, s, qa, qb, qc);
+    if (p->kind == 62) return flexcyl_f2(p, s, q);
     if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
     if ((p->kind >= 25 && p->kind <= 28) || p->kind == 57 || p->kind == 58) return sphere_family_f2(p, s, q);
     if (p->kind == 45) {
@@ -1420,6 +1492,9 @@ double orc_mean_volume(const orc_params* p)
         double phi2 = p->extra[0], phi1 = p->phi - phi2;
         return p->phi / (phi1 / vol_sphere(s[0]) + phi2 / vol_sphere(s[1]));
     }
+    case 62: /* flexible elliptical cylinder: pi eps R^2 L */
+        return ORC_PI * p->extra[1] * s[0] * s[0] * s[1]
+             * size_moment(p, (p->poly_mask & 1 ? 2 : 0) + (p->poly_mask & 2 ? 1 : 0));
     case 61: /* pringle: the plate's area times its thickness */
         return ORC_PI * s[0] * s[0] * s[1] * size_moment(p, (p->poly_mask & 1 ? 2 : 0) + (p->poly_mask & 2 ? 1 : 0));
     case 58: /* pearl necklace: N pearls and N - 1 rods */

@@ -436,6 +436,16 @@ def poly_sep_parallelepiped() -> dict:
                               poly_sep=(0.1, 0.2, 0.3)))
 
 
+def flexible_cylinder_elliptical() -> dict:
+    """Flexible cylinders with an elliptical cross-section (one of the models
+    the paper's GPU runs fastest against MPI): contour length 1000 A, Kuhn
+    length 100 A, minor radius 20 A, axis ratio 1.5, the chain and section
+    integrals by 48-point rules, 256x256, 1e8 neutrons."""
+    return dict(name="flexible_cylinder_elliptical", n=10**8, seed=23, exp_id=0,
+                params=params(kind="flexible_cylinder_elliptical", size=(20.0, 1000.0, 0), sld=(1e-6, 0, 0),
+                              phi=0.01, extra=(100.0, 1.5, 0, 0), quad_n=48, nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -471,6 +481,7 @@ WORKLOADS = {
     "oriented_pringle": oriented_pringle,
     "attenuated_coreshell": attenuated_coreshell,
     "poly_sep_cylinder": poly_sep_cylinder,
+    "flexible_cylinder_elliptical": flexible_cylinder_elliptical,
     "poly_sep_parallelepiped": poly_sep_parallelepiped,
 }
 
