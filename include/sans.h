@@ -255,7 +255,7 @@ typedef enum {
                                     (A): phi (3/R) 2 pi (drho shell)^2
                                     exp(-(q extra[0])^2) / q^2; monodisperse,
                                     no structure factor                       */
-    SANS_PRINGLE = 61            /* oriented: a plate of thickness size[1] over
+    SANS_PRINGLE = 61,           /* oriented: a plate of thickness size[1] over
                                     the disc of radius size[0] in the AB plane,
                                     bent into the saddle z = extra[0] x^2 -
                                     extra[1] y^2 (1/A); its disc integral by a
@@ -263,6 +263,20 @@ typedef enum {
                                     2 quad_n-point angular midpoint rule per
                                     event; no quadrature mode; poly_mask bits
                                     0 (radius) and 1 (thickness)              */
+    SANS_FLEXIBLE_CYLINDER_ELLIPTICAL = 62  /* isotropic: a semiflexible chain
+                                    of contour length size[1] and Kuhn length
+                                    extra[0] > 0 whose cross-section is an
+                                    ellipse of semi-axes size[0] and extra[1]
+                                    size[0] (extra[1] > 0); F^2 = (drho pi
+                                    extra[1] size[0]^2 size[1])^2 P_chain
+                                    P_cs, P_chain Kholodenko's closed form for
+                                    the wormlike chain (Macromolecules 26,
+                                    4179 (1993)), P_cs the ellipse's
+                                    [2 J1(q r)/(q r)]^2 averaged over the
+                                    in-plane angle, both integrals by
+                                    quad_n-point Gauss-Legendre per event;
+                                    Monte Carlo mode only; poly_mask bits 0
+                                    (radius) and 1 (length)                   */
 } sans_kind;
 
 /* Structure factor S(q) of the particles (when sq_phi > 0): volume fraction

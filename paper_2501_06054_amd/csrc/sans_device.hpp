@@ -170,6 +170,8 @@ struct TraceArgs {
     // spacing spread and count in sd_d, sd_sig, sf_n; the Caille exponents'
     // gamma + ln(pi n) in cap_nodes)
     float lam_c, lam_eta;
+    // flexible elliptical cylinder: Kuhn length (A) and the section's axis ratio
+    float fc_b, fc_eps;
     // run
     uint64_t first, n;
     uint32_t seed_lo, seed_hi, exp_id;
@@ -604,7 +606,7 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kMassSurfaceFractal = 49, kGelFit = 50, kSuperball = 51, kLamellarHg = 52,
               kLamellarStackCaille = 53, kLamellarHgStackCaille = 54, kLamellarStackParacrystal = 55,
               kBicelleBeltRough = 56, kRaspberry = 57, kPearlNecklace = 58, kBinaryHardSphere = 59,
-              kAdsorbedLayer = 60, kPringle = 61 };
+              kAdsorbedLayer = 60, kPringle = 61, kFlexCylEll = 62 };
 
 // Randomly oriented lamellae: the weight per unit volume fraction.
 template <int KIND>
@@ -1352,8 +1354,8 @@ __device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, cons
     } else if constexpr (KIND == kScParacrystal || KIND == kBccParacrystal || KIND == kFccParacrystal) {
         const float r = (float)s[0];
         return a.contrast * k43pi * r * r * r * sph3j_d(q * s[0]);
-    } else if constexpr (KIND == kPringle) {
-        return 0.0f;   // |F|^2 comes from pringle_f2 (F is complex)
+    } else if constexpr (KIND == kPringle || KIND == kFlexCylEll) {
+        return 0.0f;   // F^2 comes from pringle_f2 / flexcyl_f2
     } else if constexpr (KIND == kSuperball) {
         const float r = (float)s[0];
         return a.contrast * r * r * r * superball_sum(a, (float)(qa * s[0]), (float)(qb * s[0]), (float)(qc * s[0]));
@@ -1480,8 +1482,8 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
         return (float)kPi * __builtin_fmaf(a.cs_core, core, a.cs_shell * outer);
     } else if constexpr (KIND == kScParacrystal || KIND == kBccParacrystal || KIND == kFccParacrystal) {
         return a.contrast * k43pi * s[0] * s[0] * s[0] * sph3j_f(q * s[0]);
-    } else if constexpr (KIND == kPringle) {
-        return 0.0f;   // no quadrature mode for the pringle (refused at validation)
+    } else if constexpr (KIND == kPringle || KIND == kFlexCylEll) {
+        return 0.0f;   // no quadrature mode for these (refused at validation)
     } else if constexpr (KIND == kSuperball) {
         return a.contrast * s[0] * s[0] * s[0] * superball_sum(a, qa * s[0], qb * s[0], qc * s[0]);
     } else if constexpr (KIND == kCoreShellParallelepiped) {
@@ -1658,6 +1660,59 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
 }
 
 // ---------------------------------------------------------------- one neutron
+// Flexible cylinder with an elliptical cross-section: (drho V)^2 P_chain
+// P_cs with V = pi eps R^2 L.  P_chain by Kholodenko's closed form for the
+// wormlike chain: x = 3 L/b, (2/x)(I_1 - I_2/x), I_n = int_0^x f(z) z^(n-1)
+// dz, f = sinh(E z)/(E sinh z), E = sqrt(1 - (q b/3)^2), below q b = 3 and
+// sin(F z)/(F sinh z), F = sqrt((q b/3)^2 - 1), above, both integrals by the
+// n-point Gauss-Legendre rule on [0, x_e] (x_e = min(x, 40/(1 - E)) or
+// min(x, 40): the integrands fall as exp(-(1 - E) z) and exp(-z)), f written
+// without overflow as exp((E - 1) z) (1 - e^(-2 E z))/(E (1 - e^(-2 z)));
+// P_cs the average of [2 J1(q r)/(q r)]^2 over the in-plane angle psi,
+// r = R sqrt(sin^2 psi + eps^2 cos^2 psi), by the same rule.  cap_nodes:
+// [t_k, w_k] on [0, 1] (n each), then [sin^2 psi_k, cos^2 psi_k, w_k/...]
+// with the section's weights summing to 1.
+__device__ __forceinline__ float flexcyl_f2(const TraceArgs& a, double Rd, double Ld, double qd)
+{
+    const int n = a.cap_n;
+    const float* __restrict__ t = a.cap_nodes;
+    const float* __restrict__ tw = a.cap_nodes + n;
+    const float* __restrict__ s2 = a.cap_nodes + 2 * n;
+    const float* __restrict__ c2 = a.cap_nodes + 3 * n;
+    const float* __restrict__ sw = a.cap_nodes + 4 * n;
+    const float R = (float)Rd, L = (float)Ld, q = (float)qd, b = a.fc_b, eps = a.fc_eps;
+    const float x = 3.0f * L / b, v = q * b * (1.0f / 3.0f);
+    const bool below = v < 1.0f;
+    const float E = below ? sqrtf(1.0f - v * v) : 0.0f, F = below ? 0.0f : sqrtf(v * v - 1.0f);
+    const float em1 = -v * v / (1.0f + E);           // E - 1 without cancellation
+    float xe = x;
+    if (below && em1 < 0.0f) xe = fminf(xe, -40.0f / em1);
+    if (!below) xe = fminf(xe, 40.0f);
+    float i1 = 0.0f, i2 = 0.0f;
+    for (int k = 0; k < n; ++k) {
+        const float z = xe * t[k], wz = xe * tw[k];
+        const float den = -expm1f(-2.0f * z);
+        float f;
+        if (below) {
+            const float num = E > 0.0f ? -expm1f(-2.0f * E * z) / E : 2.0f * z;
+            f = expf(em1 * z) * num / den;
+        } else {
+            f = 2.0f * (F > 0.0f ? sinf(F * z) / F : z) * expf(-z) / den;
+        }
+        i1 = __builtin_fmaf(wz, f, i1);
+        i2 = __builtin_fmaf(wz * f, z, i2);
+    }
+    const float chain = 2.0f / x * (i1 - i2 / x);
+    float sec = 0.0f;
+    for (int k = 0; k < n; ++k) {
+        const float r = R * sqrtf(__builtin_fmaf(eps * eps, c2[k], s2[k]));
+        const float l = lambda1_f(q * r);
+        sec = __builtin_fmaf(sw[k], l * l, sec);
+    }
+    const float fv = a.contrast * (float)kPi * eps * R * R * L;
+    return fv * fv * chain * sec;
+}
+
 // ---------------------------------------------------------------- geometry
 // One neutron's flight (A3-A6, A12): the chord through the slab, |Q|, the
 // pixel, and what the weight and the attenuation need.
@@ -1954,6 +2009,9 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
             f2 = lamellar_f2<KIND>(a, qd);
         } else if constexpr (KIND == kPringle) {
             f2 = pringle_f2(a, (a.poly_mask & 1) ? y : 1.0, (a.poly_mask & 2) ? y : 1.0, qa, qb, qc);
+        } else if constexpr (KIND == kFlexCylEll) {
+            f2 = flexcyl_f2(a, (a.poly_mask & 1) ? a.size[0] * y : a.size[0],
+                            (a.poly_mask & 2) ? a.size[1] * y : a.size[1], qd);
         } else if constexpr (kSphereFamily<KIND>) {
             f2 = sphere_family_f2<KIND>(a, (a.poly_mask & 1) ? a.size[0] * y : a.size[0], qd);
         } else {

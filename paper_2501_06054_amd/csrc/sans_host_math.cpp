@@ -359,6 +359,12 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
         const int kg[3] = {b0 ? 1 : 0, b0 ? 1 : 0, 0};
         return kPiH * expand_moment(f, k, poly_kind, poly) + 2.0 * kPiH * extra[0] * expand_moment(g, kg, poly_kind, poly);
     }
+    case 62: {
+        // flexible elliptical cylinder: pi eps (R y^b0)^2 (L y^b1)
+        const double f[3][2] = {{size[0], 0.0}, {size[0], 0.0}, {size[1], 0.0}};
+        const int k[3] = {b0 ? 1 : 0, b0 ? 1 : 0, b1 ? 1 : 0};
+        return kPiH * extra[1] * expand_moment(f, k, poly_kind, poly);
+    }
     case 61: {
         // pringle: pi (R y^b0)^2 (t y^b1)
         const double f[3][2] = {{size[0], 0.0}, {size[0], 0.0}, {size[1], 0.0}};

@@ -400,6 +400,7 @@ size_t rule_floats(const sans_params& p)
     if (p.kind == SANS_PEARL_NECKLACE) return 2 * (size_t)p.quad_n;
     if (p.kind == SANS_BINARY_HARD_SPHERE) return 4 * 32;
     if (p.kind == SANS_PRINGLE) return 8 * (size_t)p.quad_n * p.quad_n;
+    if (p.kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL) return 5 * (size_t)p.quad_n;
     if (p.kind == SANS_POLYMER_EXCL_VOLUME) return 4 * (size_t)kPevRuleNodes;
     return 0;
 }
@@ -433,6 +434,20 @@ void fill_nodes(const sans_params& p, float* out, const float* base, TraceArgs& 
                 out[2 * h * n + k] = (float)std::pow(w, 6.0);
                 out[(2 * h + 1) * n + k] = (float)(6.0 * 0.5 * gw[k] * std::pow(w, 6.0 * sv[h] - 1.0));
             }
+    } else if (p.kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL) {
+        // the chain's rule on [0, 1] (scaled to [0, x_e] per event) and the
+        // section's angle psi in [0, pi/2] (weights of the average, sum 1)
+        const int n = p.quad_n;
+        std::vector<double> gx(n), gw(n);
+        host::gauss_legendre(n, gx.data(), gw.data());
+        for (int k = 0; k < n; ++k) {
+            const double psi = 0.25 * kPi * (gx[k] + 1.0);
+            out[k] = (float)(0.5 * (gx[k] + 1.0));
+            out[n + k] = (float)(0.5 * gw[k]);
+            out[2 * n + k] = (float)(std::sin(psi) * std::sin(psi));
+            out[3 * n + k] = (float)(std::cos(psi) * std::cos(psi));
+            out[4 * n + k] = (float)(0.5 * gw[k]);
+        }
     } else if (p.kind == SANS_PRINGLE) {
         // polar rule on the disc: r by n-point Gauss-Legendre on [0, R], the
         // angle by the 2n-point midpoint rule on [0, pi); (x, y) pairs with
@@ -518,7 +533,7 @@ int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 61) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (p->kind < 0 || p->kind > 62) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -538,7 +553,8 @@ int validate(const sans_params* p)
                            || p->kind == SANS_BCC_PARACRYSTAL || p->kind == SANS_FCC_PARACRYSTAL
                            || p->kind == SANS_LAMELLAR_HG || p->kind == SANS_LAMELLAR_STACK_CAILLE
                            || p->kind == SANS_LAMELLAR_STACK_PARACRYSTAL
-                           || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH || p->kind == SANS_PRINGLE;
+                           || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH || p->kind == SANS_PRINGLE
+                           || p->kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL;
     int nsize = (p->kind <= 1 || p->kind == SANS_SUPERBALL || p->kind == SANS_ADSORBED_LAYER) ? 1 : (two_sizes ? 2 : 3);
     if (is_shape_independent(p->kind))
         nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK
@@ -569,6 +585,14 @@ int validate(const sans_params* p)
             return fail(SANS_E_UNSUPPORTED, "pringle: no quadrature mode (2 quad_n^2 nodes per orientation node)");
         if (p->poly > 0.0 && (p->poly_mask & 4))
             return fail(SANS_E_UNSUPPORTED, "pringle: poly_mask bits 0 (radius) and 1 (thickness) only");
+    }
+    if (p->kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL) {
+        if (!(p->extra[0] > 0.0 && finite(p->extra[0]) && p->extra[1] > 0.0 && finite(p->extra[1])))
+            return fail(SANS_E_INVALID_ARG, "flexible cylinder: Kuhn length extra[0] and axis ratio extra[1] must be > 0");
+        if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
+        if (p->mode != SANS_MODE_MC) return fail(SANS_E_UNSUPPORTED, "flexible cylinder: Monte Carlo mode only");
+        if (p->poly > 0.0 && (p->poly_mask & 4))
+            return fail(SANS_E_UNSUPPORTED, "flexible cylinder: poly_mask bits 0 (radius) and 1 (length) only");
     }
     if (p->kind == SANS_ADSORBED_LAYER) {
         if (!(p->shell > 0.0 && finite(p->shell) && p->extra[0] >= 0.0 && finite(p->extra[0])))
@@ -1132,6 +1156,11 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     }
     if (p->kind == SANS_SUPERBALL) a.cap_n = p->quad_n;
     if (p->kind == SANS_PRINGLE) a.cap_n = p->quad_n;
+    if (p->kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL) {
+        a.cap_n = p->quad_n;
+        a.fc_b = (float)p->extra[0];
+        a.fc_eps = (float)p->extra[1];
+    }
     if (p->kind == SANS_ADSORBED_LAYER) {
         a.lam_c = (float)(6.0 * kPi / p->size[0]);
         a.sd_sig = p->extra[0];
@@ -2128,6 +2157,7 @@ double model_cost(const sans_params& p)
     case SANS_CAPPED_CYLINDER: return 1.0 + 43.0 * n / 900.0;
     case SANS_SUPERBALL: return 1.0 + (19.0 * n + 38.0 * n * n) / 900.0;
     case SANS_PRINGLE: return 1.0 + 36.0 * 2.0 * n * n / 900.0;
+    case SANS_FLEXIBLE_CYLINDER_ELLIPTICAL: return 0.7 + 40.0 * n / 900.0;
     case SANS_PEARL_NECKLACE: return 1.0 + (55.0 * n + 8.0 * p.extra[0]) / 900.0;
     case SANS_LAMELLAR_STACK_CAILLE:
     case SANS_LAMELLAR_HG_STACK_CAILLE:

@@ -72,6 +72,10 @@ def _create_status(S, p):
           mode="quad", orient_kind="isotropic"), -2),
     (dict(kind="sphere", poly_kind="gaussian", poly_sep=(-0.1, 0, 0)), -1),
     (dict(kind="sphere", poly_kind="gaussian", poly_sep=(1.5, 0, 0)), -1),
+    # flexible elliptical cylinder: Kuhn length, axis ratio, Monte Carlo mode only
+    (dict(kind="flexible_cylinder_elliptical", size=(20.0, 1000.0, 0), extra=(0.0, 1.5, 0, 0)), -1),
+    (dict(kind="flexible_cylinder_elliptical", size=(20.0, 1000.0, 0), extra=(100.0, -1.0, 0, 0)), -1),
+    (dict(kind="flexible_cylinder_elliptical", size=(20.0, 1000.0, 0), extra=(100.0, 1.5, 0, 0), mode="quad"), -2),
 ])
 def test_invalid_params_rejected_without_gpu(S, over, status):
     from paper_2501_06054_amd import workloads as W
@@ -220,7 +224,7 @@ def test_capped_body_params_rejected_without_gpu(S, over, code):
 def test_unknown_kind_rejected_without_gpu(S):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(kind="hollow_prism", size=(20.0, 40.0, 60.0), shell=1.0))
-    sp.kind = 62
+    sp.kind = max(S.KIND.values()) + 1
     h = C.c_void_p()
     assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED
 

@@ -305,6 +305,13 @@ PER_NEUTRON = {
                                           orient_mean=(1.2, 0.4, 0.8), orient_sigma=(0.2, 0.1, 0.3)), 20011),
     "poly_sep_ellcyl_iso": (W.params(kind="elliptical_cylinder", size=(20.0, 35.0, 300.0), poly_kind="gaussian",
                                      poly_sep=(0.1, 0.0, 0.2), orient_kind="isotropic"), 20011),
+    # flexible cylinder with an elliptical cross-section
+    "flexible_cylinder_elliptical": (W.workload("flexible_cylinder_elliptical")["params"], 20011),
+    "flexcyl_poly_stiff": (W.params(kind="flexible_cylinder_elliptical", size=(15.0, 600.0, 0),
+                                    extra=(2000.0, 1.0, 0, 0), quad_n=32, poly=0.2, poly_mask=3), 20011),
+    "flexcyl_flexible_flat": (W.params(kind="flexible_cylinder_elliptical", size=(10.0, 3000.0, 0),
+                                       extra=(40.0, 3.0, 0, 0), quad_n=64, poly=0.15, poly_mask=1,
+                                       poly_kind="gaussian"), 20011),
     # sample attenuation
     "attenuated_coreshell": (dict(W.workload("coreshell_py")["params"], mu_att=150.0), 30011),
     "attenuated_wide_cone_cylinder": (W.params(kind="cylinder", size=(20.0, 200.0, 0), orient_kind="isotropic",
@@ -348,7 +355,8 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "oriented_superball", "lamellar_caille", "lamellar_hg", "lamellar_stack_paracrystal",
              "belt_bicelle_gauss", "raspberry_poly", "pearl_necklace", "binary_hard_sphere",
              "adsorbed_layer", "pringle_iso", "attenuated_coreshell", "poly_sep_cylinder",
-             "poly_sep_parallelepiped", "poly_sep_ellipsoid_gauss"]
+             "poly_sep_parallelepiped", "poly_sep_ellipsoid_gauss", "flexible_cylinder_elliptical",
+             "flexcyl_flexible_flat"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -520,7 +528,7 @@ def test_full_size_independent_widths(S, name):
                                   "teubner_strey", "sticky_coreshell", "mass_surface_fractal", "lamellar_caille",
                                   "pearl_necklace", "polymer_excl_volume", "binary_hard_sphere",
                                   "raspberry", "oriented_belt_bicelle", "adsorbed_layer",
-                                  "attenuated_coreshell"])
+                                  "attenuated_coreshell", "flexible_cylinder_elliptical"])
 def test_full_size_sampled(S, name):
     """1e9- and 1e8-neutron workloads: the full run equals the sum of its chunks, and
     windows spread over the whole index range match the oracle neutron by
