@@ -38,7 +38,7 @@ KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelep
         "raspberry": 57, "pearl_necklace": 58, "binary_hard_sphere": 59, "adsorbed_layer": 60,
         "pringle": 61,
         "flexible_cylinder_elliptical": 62}
-SQ_KIND = {"hard_sphere": 0, "sticky_hard_sphere": 1, "square_well": 2}
+SQ_KIND = {"hard_sphere": 0, "sticky_hard_sphere": 1, "square_well": 2, "hayter_msa": 3}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}
 POLY_KIND = {"schulz": 0, "gaussian": 1}
@@ -99,7 +99,12 @@ def trace_native(so_path: str, p: dict, n: int, seed: int, first: int = 0, exp_i
         L.orc_trace.argtypes = [P(OrcParams), C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, C.c_int32,
                                 P(C.c_double), P(C.c_double), P(C.c_uint64)]
         L.orc_trace.restype = C.c_int32
+        L.orc_set_msa.argtypes = [P(C.c_double), C.c_double, C.c_double, C.c_double]
         _NATIVE[so_path] = L
+    if p.get("sq_kind") == "hayter_msa" and p.get("sq_phi", 0.0) > 0.0:
+        from oracle import msa
+        c = np.ascontiguousarray(msa.inside_c(float(p["sq_phi"]), float(p["sq_extra"][0]), float(p["sq_extra"][1])))
+        L.orc_set_msa(_ptr(c, C.c_double), float(p["sq_phi"]), float(p["sq_extra"][0]), float(p["sq_extra"][1]))
     o = to_params(p)
     det = np.zeros((p["ny"], p["nx"]))
     rc = L.orc_trace(C.byref(o), first, n, seed, exp_id, nthreads, _ptr(det, C.c_double), None, None)
@@ -138,6 +143,9 @@ def lib():
         L.orc_flexcyl_chain.restype = d
         L.orc_flexcyl_section.argtypes = [d, d, d, i32]
         L.orc_flexcyl_section.restype = d
+        L.orc_set_msa.argtypes = [P(d), d, d, d]
+        L.orc_msa_sq.argtypes = [d, d, d, d, d]
+        L.orc_msa_sq.restype = d
         L.orc_sticky_lambda.argtypes = [d, d]
         L.orc_sticky_lambda.restype = d
         L.orc_sticky_sq.argtypes = [d, d, d, d]
@@ -362,10 +370,29 @@ def form_f2(p: dict, q: float, qvec, y: float = 1.0, angles=None) -> float:
     return lib().orc_form_f2(C.byref(o), q, _ptr(qv, C.c_double), y, _ptr(ang, C.c_double))
 
 
+def _prepare(p: dict) -> None:
+    """Per-parameter-set set-up outside the C tracer: the Hayter-Penfold
+    direct correlation function inside the core."""
+    if p.get("sq_kind") == "hayter_msa" and p.get("sq_phi", 0.0) > 0.0:
+        set_msa(p["sq_phi"], p["sq_extra"][0], p["sq_extra"][1])
+
+
+def set_msa(eta: float, uc: float, ks: float) -> None:
+    from oracle import msa
+    c = np.ascontiguousarray(msa.inside_c(float(eta), float(uc), float(ks)))
+    lib().orc_set_msa(_ptr(c, C.c_double), float(eta), float(uc), float(ks))
+
+
+def msa_sq(q: float, radius: float, eta: float, uc: float, ks: float) -> float:
+    """The Hayter-Penfold S(q) of the C oracle (after set_msa)."""
+    return lib().orc_msa_sq(q, radius, eta, uc, ks)
+
+
 def trace(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0, nthreads: int = 1,
           with_w2: bool = False, with_count: bool = False):
     """Detector (ny, nx) FP64 of neutrons first..first+n-1; optionally the
     sum of w^2 and the hit counts."""
+    _prepare(p)
     o = to_params(p)
     det = np.zeros((p["ny"], p["nx"]))
     w2 = np.zeros_like(det) if with_w2 else None
@@ -382,6 +409,7 @@ def trace(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0, nthreads:
 
 def trace_debug(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0):
     """Per-neutron (pixel, w, q): pixel -1 and w 0 when nothing is tallied."""
+    _prepare(p)
     o = to_params(p)
     pix = np.zeros(n, dtype=np.int32)
     w = np.zeros(n)
@@ -397,6 +425,7 @@ def trace_debug_ex(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0) 
     """Per-neutron intermediates [n, 14]: pixel, w, q, Q_x, Q_y, Q_z, y,
     theta, phi, Psi, path length (m), and the independent size factors
     y_0, y_1, y_2 (1 where a size has no width of its own)."""
+    _prepare(p)
     o = to_params(p)
     out = np.zeros((n, 14))
     rc = lib().orc_trace_debug_ex(C.byref(o), first, n, seed, exp_id, _ptr(out, C.c_double))

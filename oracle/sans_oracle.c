@@ -486,9 +486,46 @@ double orc_square_well_sq(double q, double radius, double eta, double depth, dou
 }
 
 /* The structure factor selected by sq_kind (1 when sq_phi = 0). */
+/* Hayter-Penfold structure factor (sq_kind 3): charged hard spheres of
+ * diameter sigma = 2 sq_radius with beta U = U_c (sigma/r) exp(-kappa (r -
+ * sigma)) outside the core (U_c = sq_extra[0], kappa sigma = sq_extra[1]) in
+ * the mean spherical approximation.  The direct correlation function inside
+ * the core, c(x) at x = i/ORC_MSA_N (i = 0..ORC_MSA_N, units of sigma), comes
+ * from the oracle's Ornstein-Zernike solver (oracle/msa.py) through
+ * orc_set_msa; here S = 1/(1 - rho c^(K)), K = q sigma, rho = 6 eta/pi, with
+ * c^ = 4 pi/K int_0^1 x c sin(K x) dx by Simpson on the grid plus the tail's
+ * closed form -4 pi U_c (k sin K + K cos K)/(K (k^2 + K^2)), k = kappa sigma. */
+#define ORC_MSA_N 1024
+static double g_msa_c[ORC_MSA_N + 1];
+static double g_msa_key[3] = {-1.0, -1.0, -1.0};
+
+void orc_set_msa(const double* c_in, double eta, double uc, double ks)
+{
+    memcpy(g_msa_c, c_in, sizeof(double) * (ORC_MSA_N + 1));
+    g_msa_key[0] = eta;
+    g_msa_key[1] = uc;
+    g_msa_key[2] = ks;
+}
+
+double orc_msa_sq(double q, double radius, double eta, double uc, double ks)
+{
+    if (g_msa_key[0] != eta || g_msa_key[1] != uc || g_msa_key[2] != ks) return NAN;  /* not set up */
+    const double K = 2.0 * radius * q, h = 1.0 / ORC_MSA_N;
+    double inner = 0.0;
+    for (int i = 0; i <= ORC_MSA_N; ++i) {
+        const double w = (i == 0 || i == ORC_MSA_N) ? 1.0 : (i % 2 ? 4.0 : 2.0);
+        const double x = i * h;
+        inner += w * x * g_msa_c[i] * sin(K * x);
+    }
+    inner *= h / 3.0 * 4.0 * ORC_PI / K;
+    const double tail = -4.0 * ORC_PI * uc * (ks * sin(K) + K * cos(K)) / (K * (ks * ks + K * K));
+    return 1.0 / (1.0 - 6.0 * eta / ORC_PI * (inner + tail));
+}
+
 static double struct_factor(const orc_params* p, double q)
 {
     if (!(p->sq_phi > 0.0)) return 1.0;
+    if (p->sq_kind == 3) return orc_msa_sq(q, p->sq_radius, p->sq_phi, p->sq_extra[0], p->sq_extra[1]);
     if (p->sq_kind == 1) return orc_sticky_sq(q, p->sq_radius, p->sq_phi, p->sq_extra[0]);
     if (p->sq_kind == 2) return orc_square_well_sq(q, p->sq_radius, p->sq_phi, p->sq_extra[0], p->sq_extra[1]);
     return orc_py_sq(q, p->sq_radius, p->sq_phi);
