@@ -72,6 +72,9 @@ STEP = {
     "sticky_sq": 50, "msf_I": 10, "sb_row": 22, "sb_node": 44, "lam_hg_F": 30, "caille_term": 24,
     "neck_node": 44, "neck_unit": 12, "bhs_node": 20, "bhs_mat": 40, "rasp_F": 60, "belt_F": 80,
     "ads_I": 8, "pr_node": 40, "attenuation": 1,
+    "fc_chain_node": 28,  # flexible cylinder, one node of the chain rule: exp, expm1, the two sums
+    "cyl_section": 20,    # [2 J1(qR)/(qR)]^2, series or asymptotic form
+    "msa_sq": 12,        # Hayter-Penfold S: knot index, cubic Hermite between two knots
     "fc_node": 40,       # flexible cylinder, one node of the chain and section rules: exp, expm1, a sine,
                          # the two chain sums; the section's radius (sqrt) and 2 J1(x)/x series
     "weight": 3,         # A11
@@ -134,6 +137,9 @@ PATHS = {
                                + ["size_draw"] * 3 + ["qvec", "iso_orient", "project_abc", "box_F"],
     # flexible elliptical cylinder: 48-point chain and section rules
     "flexible_cylinder_elliptical": COMMON + ["philox_block"] * 2 + ["uniform"] * 8 + ["fc_node"] * 48,
+    "flexible_cylinder": COMMON + ["philox_block"] * 3 + ["uniform"] * 9 + ["size_draw"]
+                         + ["fc_chain_node"] * 48 + ["cyl_section"],
+    "charged_spheres": COMMON + ["philox_block"] * 3 + ["uniform"] * 9 + ["size_draw", "sphere_F", "msa_sq"],
     "oriented_pringle": COMMON + ["philox_block"] * 3 + ["uniform"] * 11
                         + ["qvec", "iso_orient", "project_abc"] + ["pr_node"] * 512,
 }

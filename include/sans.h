@@ -263,7 +263,7 @@ typedef enum {
                                     2 quad_n-point angular midpoint rule per
                                     event; no quadrature mode; poly_mask bits
                                     0 (radius) and 1 (thickness)              */
-    SANS_FLEXIBLE_CYLINDER_ELLIPTICAL = 62  /* isotropic: a semiflexible chain
+    SANS_FLEXIBLE_CYLINDER_ELLIPTICAL = 62, /* isotropic: a semiflexible chain
                                     of contour length size[1] and Kuhn length
                                     extra[0] > 0 whose cross-section is an
                                     ellipse of semi-axes size[0] and extra[1]
@@ -274,6 +274,14 @@ typedef enum {
                                     4179 (1993)), P_cs the ellipse's
                                     [2 J1(q r)/(q r)]^2 averaged over the
                                     in-plane angle, both integrals by
+                                    quad_n-point Gauss-Legendre per event;
+                                    Monte Carlo mode only; poly_mask bits 0
+                                    (radius) and 1 (length)                   */
+    SANS_FLEXIBLE_CYLINDER = 63, /* isotropic: the same chain with a circular
+                                    cross-section of radius size[0]
+                                    (extra[1] unused): F^2 = (drho pi
+                                    size[0]^2 size[1])^2 P_chain
+                                    [2 J1(q R)/(q R)]^2; chain integrals by
                                     quad_n-point Gauss-Legendre per event;
                                     Monte Carlo mode only; poly_mask bits 0
                                     (radius) and 1 (length)                   */
@@ -288,12 +296,25 @@ typedef enum {
                                     sq_extra[0] > 0; SANS_E_DOMAIN where no
                                     solution exists (tau below the two-phase
                                     boundary)                                  */
-    SANS_SQ_SQUARE_WELL = 2      /* square-well fluid, mean spherical
+    SANS_SQ_SQUARE_WELL = 2,     /* square-well fluid, mean spherical
                                     approximation: well depth sq_extra[0] (kT,
                                     attractive when > 0) from sigma out to
                                     sq_extra[1] sigma (width in [1, 4]);
                                     SANS_E_DOMAIN where 1/S(q) <= 0 inside the
                                     instrument's q range                       */
+    SANS_SQ_HAYTER_MSA = 3       /* Hayter-Penfold charged spheres: hard core
+                                    plus the screened Coulomb repulsion
+                                    U_c (sigma/r) exp(-kappa (r - sigma)) in
+                                    the mean spherical approximation, contact
+                                    potential U_c = sq_extra[0] (kT, in
+                                    [0, 50]) and screening kappa sigma =
+                                    sq_extra[1] (in (0, 50]).  The Ornstein-
+                                    Zernike equation is solved on a radial
+                                    grid when the parameters are set (about a
+                                    second per U_c = 5; cached by eta, U_c,
+                                    kappa sigma) and S tabulated over the
+                                    instrument's q range; SANS_E_DOMAIN where
+                                    the solver finds no physical solution     */
 } sans_sq_kind;
 
 /* How the particle size and orientation enter the weight. */

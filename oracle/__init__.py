@@ -37,7 +37,7 @@ KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelep
         "lamellar_stack_paracrystal": 55, "core_shell_bicelle_elliptical_belt_rough": 56,
         "raspberry": 57, "pearl_necklace": 58, "binary_hard_sphere": 59, "adsorbed_layer": 60,
         "pringle": 61,
-        "flexible_cylinder_elliptical": 62}
+        "flexible_cylinder_elliptical": 62, "flexible_cylinder": 63}
 SQ_KIND = {"hard_sphere": 0, "sticky_hard_sphere": 1, "square_well": 2, "hayter_msa": 3}
 ORIENT = {"fixed": 0, "gaussian": 1, "isotropic": 2, "uniform_angles": 3}
 MODE = {"mc": 0, "quad": 1, "surrogate": 2}

@@ -15,8 +15,12 @@ i < N = 65536 (to x = 64), the three-dimensional Fourier transforms as
 sine transforms (SciPy's DST-I), iterating on gamma = h - c: c = -1 - gamma
 inside the core, -beta U outside, the mean of the two at x = 1 (the jump);
 c^ = transform of c; gamma^ = rho c^2 / (1 - rho c^); gamma = inverse
-transform of gamma^; 50 damped Picard steps, then Anderson mixing, until
-gamma changes by less than 1e-12 (the solution must keep 1 - rho c^ > 0).
+transform of gamma^.  The fixed point is followed from the uncharged
+spheres (U_c = 0, the Percus-Yevick hard spheres) up to the given U_c in
+equal steps of at most 1 in U_c, each solved by Anderson mixing (6
+differences, mixing 0.3) from the previous stage's gamma, to 1e-8 on the
+way and until gamma changes by less than 1e-12 at the end; every iterate
+must keep 1 - rho c^ > 0 (the physical branch), else the solver fails.
 The structure factor at any K = q sigma is then S = 1 / (1 - rho c^(K))
 with c^ = 4 pi / K int_0^1 x c(x) sin(K x) dx (Simpson on the grid's 1024
 intervals) plus the tail's closed form
@@ -39,7 +43,7 @@ def _tail(x, uc, ks):
 
 
 @lru_cache(maxsize=16)
-def inside_c(eta: float, uc: float, ks: float, tol: float = 1e-12, max_iter: int = 4000,
+def inside_c(eta: float, uc: float, ks: float, tol: float = 1e-12, max_iter: int = 400,
              nin: int = NIN, n: int = N) -> np.ndarray:
     """c(x) on the core's grid x_i = i/nin, i = 0..nin (the value at x = 1
     is the inside limit, -1 - gamma(1)); the solver's grid has n points of
@@ -55,50 +59,56 @@ def inside_c(eta: float, uc: float, ks: float, tol: float = 1e-12, max_iter: int
     inside, at1 = x < 1.0 - 0.5 * h, np.abs(x - 1.0) < 0.5 * h
     u = np.where(x > 1.0, _tail(x, uc, ks), 0.0)
 
-    def closure(g):
-        c = np.where(inside, -1.0 - g, -u)
-        c[at1] = 0.5 * ((-1.0 - g[at1]) + (-uc))
+    def closure(g, us):
+        c = np.where(inside, -1.0 - g, -us * u)
+        c[at1] = 0.5 * ((-1.0 - g[at1]) + (-us * uc))
         return c
 
-    def step(g):
-        c = closure(g)
+    def step(g, us):
+        """gamma -> the next gamma at the contact potential us * U_c, or None
+        when 1 - rho c^ <= 0 somewhere (off the physical branch)."""
+        c = closure(g, us)
         ch = 4.0 * math.pi * h / K * 0.5 * fft.dst(x * c, type=1)
-        gh = rho * ch * ch / (1.0 - rho * ch)
+        d = 1.0 - rho * ch
+        if not np.all(d > 0.0):
+            return None
+        gh = rho * ch * ch / d
         return dk / (2.0 * math.pi**2 * x) * 0.5 * fft.dst(K * gh, type=1)
 
-    # the fixed point g = step(g): 50 damped Picard steps (mixing 0.2) from
-    # g = 0, then Anderson mixing (6 differences, mixing 0.3); the warm-up
-    # keeps the iteration on the physical branch (1 - rho c^ > 0 at every K)
-    g = np.zeros(N - 1)
-    hist_g, hist_f = [], []
-    m, beta = 6, 0.3
-    for it in range(max_iter):
-        gn = step(g)
-        f = gn - g
-        err = float(np.max(np.abs(f)))
-        if err < tol:
-            g = gn
-            break
-        if it < 50:
-            g = g + 0.2 * f
-            continue
-        hist_g.append(g.copy())
-        hist_f.append(f.copy())
-        if len(hist_g) > m:
-            hist_g.pop(0)
-            hist_f.pop(0)
-        if len(hist_f) > 1:
-            dF = np.array([hist_f[k + 1] - hist_f[k] for k in range(len(hist_f) - 1)]).T
-            dG = np.array([hist_g[k + 1] - hist_g[k] for k in range(len(hist_g) - 1)]).T
-            coef, *_ = np.linalg.lstsq(dF, f, rcond=None)
-            g = g + beta * f - (dG + beta * dF) @ coef
-        else:
-            g = g + beta * f
-    else:
+    def anderson(g, us, stage_tol):
+        hist_g, hist_f = [], []
+        m, beta = 6, 0.3
+        for _ in range(max_iter):
+            gn = step(g, us)
+            if gn is None:
+                raise RuntimeError(f"MSA iterate left the physical branch (eta={eta}, U_c={uc}, kappa sigma={ks})")
+            f = gn - g
+            err = float(np.max(np.abs(f)))
+            if not math.isfinite(err):
+                break
+            if err < stage_tol:
+                return gn
+            hist_g.append(g.copy())
+            hist_f.append(f.copy())
+            if len(hist_g) > m:
+                hist_g.pop(0)
+                hist_f.pop(0)
+            if len(hist_f) > 1:
+                dF = np.array([hist_f[k + 1] - hist_f[k] for k in range(len(hist_f) - 1)]).T
+                dG = np.array([hist_g[k + 1] - hist_g[k] for k in range(len(hist_g) - 1)]).T
+                coef, *_ = np.linalg.lstsq(dF, f, rcond=None)
+                g = g + beta * f - (dG + beta * dF) @ coef
+            else:
+                g = g + beta * f
         raise RuntimeError(f"MSA iteration did not converge (eta={eta}, U_c={uc}, kappa sigma={ks})")
+
+    # continuation in the contact potential: U_c s / S for s = 1..S
+    stages = max(1, math.ceil(uc))
+    g = np.zeros(N - 1)
+    for s_ in range(1, stages + 1):
+        g = anderson(g, s_ / stages, tol if s_ == stages else max(tol, 1e-8))
     # gamma at x = 0 (the transform's limit) and on the core's grid
-    gh_final = None
-    c = closure(g)
+    c = closure(g, 1.0)
     ch = 4.0 * math.pi * h / K * 0.5 * fft.dst(x * c, type=1)
     if not np.all(1.0 - rho * ch > 0.0):
         raise RuntimeError(f"MSA solution unphysical (1 - rho c^ <= 0; eta={eta}, U_c={uc}, kappa sigma={ks})")

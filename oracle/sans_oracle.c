@@ -1321,6 +1321,16 @@ static double flexcyl_f2(const orc_params* p, const double s[3], double q)
     return v * v * flexcyl_chain(q, L, b, p->quad_n) * flexcyl_section(q, R, eps, p->quad_n);
 }
 
+/* Flexible cylinder (kind 63; named in Table I of the paper, no formula
+ * given there): the same chain with a circular cross-section of radius
+ * R = size[0], F^2 = (drho pi R^2 L)^2 P_chain(q) [2 J1(q R)/(q R)]^2. */
+static double flexcyl_round_f2(const orc_params* p, const double s[3], double q)
+{
+    const double R = s[0], L = s[1], l = orc_lambda1(q * R);
+    const double v = (p->sld[0] - p->sld[2]) * ORC_PI * R * R * L;
+    return v * v * flexcyl_chain(q, L, p->extra[0], p->quad_n) * l * l;
+}
+
 /* The squared amplitude of one particle, or for the micelle its scattering
  * per particle (it has incoherent chain terms); for the shape-independent
  * models their cross-section in 1/cm. */
@@ -1331,6 +1341,7 @@ static double form_f2(const orc_params* p, const double s[3], double q, double q
     if (p->kind == 59) return binary_hs_f2(p, s, q);
     if (p->kind == 61) return pringle_f2(p, s, qa, qb, qc);
     if (p->kind == 62) return flexcyl_f2(p, s, q);
+    if (p->kind == 63) return flexcyl_round_f2(p, s, q);
     if (p->kind == 8) return micelle_f2(s, p->sld, p->extra, q);
     if ((p->kind >= 25 && p->kind <= 28) || p->kind == 57 || p->kind == 58) return sphere_family_f2(p, s, q);
     if (p->kind == 45) {
@@ -1531,6 +1542,9 @@ double orc_mean_volume(const orc_params* p)
     }
     case 62: /* flexible elliptical cylinder: pi eps R^2 L */
         return ORC_PI * p->extra[1] * s[0] * s[0] * s[1]
+             * size_moment(p, (p->poly_mask & 1 ? 2 : 0) + (p->poly_mask & 2 ? 1 : 0));
+    case 63: /* flexible cylinder: pi R^2 L */
+        return ORC_PI * s[0] * s[0] * s[1]
              * size_moment(p, (p->poly_mask & 1 ? 2 : 0) + (p->poly_mask & 2 ? 1 : 0));
     case 61: /* pringle: the plate's area times its thickness */
         return ORC_PI * s[0] * s[0] * s[1] * size_moment(p, (p->poly_mask & 1 ? 2 : 0) + (p->poly_mask & 2 ? 1 : 0));

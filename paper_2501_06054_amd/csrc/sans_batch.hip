@@ -89,7 +89,8 @@ __global__ __launch_bounds__(kHistBlock) void k_batch(const TraceArgs* __restric
         case 59: batch_tile<59>(a, tl.first, tl.count, hist, tab); break;
         case 60: batch_tile<60>(a, tl.first, tl.count, hist, tab); break;
         case 61: batch_tile<61>(a, tl.first, tl.count, hist, tab); break;
-        default: batch_tile<62>(a, tl.first, tl.count, hist, tab); break;
+        case 62: batch_tile<62>(a, tl.first, tl.count, hist, tab); break;
+        default: batch_tile<63>(a, tl.first, tl.count, hist, tab); break;
         }
         __syncthreads();
         double* det = dets + (size_t)e * npix;

@@ -59,6 +59,9 @@ constexpr int kMaxQuad = 256;
 // 8 eta depth, width, width^3.
 constexpr int kSqA = 0, kSqB = kPySeriesTerms, kSqE = 2 * kPySeriesTerms, kSqH = kSqE + 1, kSqBb = kSqE + 2,
               kSqC0 = kSqE + 3, kSqW8 = kSqE + 4, kSqW = kSqE + 5, kSqW3 = kSqE + 6, kSqCoef = kSqE + 7;
+// Hayter-Penfold table: 1/dK, the last knot's index, two unused floats,
+// then (S, dK dS/dK) at K_j = j dK
+constexpr int kMsaHead = 4;
 
 // orientation node arrays of the exact average: mu, w_mu, cos beta, sin beta,
 // w_beta, sqrt(1 - mu^2)
@@ -105,12 +108,13 @@ struct TraceArgs {
     // k M, global memory), sep_block3 when sizes 1 or 2 draw (fourth block)
     int32_t sep_any, sep_on[3], sep_block3;
     const double* tab_sep;
-    int32_t sq_on, sq_kind;       // sq_kind: 0 hard spheres, 1 adhesive, 2 square well
+    int32_t sq_on, sq_kind;       // sq_kind: 0 hard spheres, 1 adhesive, 2 square well, 3 Hayter-Penfold
     float sq_2r, sq_24phi;
     float py_alpha, py_beta, py_gamma;
     float py_c[kPySeriesTerms];
-    // adhesive and square-well constants (device memory, kSqCoef floats; read
-    // only on their branch, so they hold no registers in the other kernels)
+    // adhesive and square-well constants (kSqCoef floats) or the Hayter-
+    // Penfold table (device memory; read only on their branch, so they hold
+    // no registers in the other kernels)
     const float* sq_coef;
     // tables (device global memory, FP64 knots; kernels stage them in LDS)
     int32_t M;                    // knots per table
@@ -497,14 +501,32 @@ __device__ __forceinline__ float sticky_sq(const float* __restrict__ c, float k)
     return rcpf(__builtin_fmaf(A, A, B * B));
 }
 
+// Hayter-Penfold S at K = q sigma: cubic Hermite between the two knots
+// around K from their values and slopes (clamped to the table's span).
+__device__ __forceinline__ float msa_sq(const float* __restrict__ c, float K)
+{
+    const float t = fminf(fmaxf(K * c[0], 0.0f), c[1]);
+    const float fk = fminf(floorf(t), c[1] - 1.0f);
+    const int k = (int)fk;
+    const float f = t - fk;
+    const float* __restrict__ e = c + kMsaHead + 2 * k;
+    const float s0 = e[0], d0 = e[1], s1 = e[2], d1 = e[3];
+    const float ds = s1 - s0;
+    const float c3 = __builtin_fmaf(-2.0f, ds, d0 + d1);
+    const float c2 = __builtin_fmaf(3.0f, ds, -__builtin_fmaf(2.0f, d0, d1));
+    return __builtin_fmaf(f, __builtin_fmaf(f, __builtin_fmaf(f, c3, c2), d0), s0);
+}
+
 // The structure factor of the model (the kind is the same for every lane):
 // hard spheres; adhesive spheres; the square well, whose mean-spherical
 // direct correlation adds 8 eta depth (w^3 Phi(w x) - Phi(x)) to the
-// hard-sphere one (Phi the sphere's 3 j1(y)/y).
+// hard-sphere one (Phi the sphere's 3 j1(y)/y); Hayter-Penfold's charged
+// spheres from their table.
 __device__ __forceinline__ float struct_factor(const TraceArgs& a, float q)
 {
     const float x = q * a.sq_2r;
     if (a.sq_kind == 1) return sticky_sq(a.sq_coef, x);
+    if (a.sq_kind == 3) return msa_sq(a.sq_coef, x);
     float inv = py_inv_sq(a, x);
     if (a.sq_kind == 2) {
         const float* __restrict__ c = a.sq_coef;
@@ -606,7 +628,7 @@ enum : int { kSphere = 0, kCoreShell = 1, kCylinder = 2, kEllipsoid = 3, kParall
               kMassSurfaceFractal = 49, kGelFit = 50, kSuperball = 51, kLamellarHg = 52,
               kLamellarStackCaille = 53, kLamellarHgStackCaille = 54, kLamellarStackParacrystal = 55,
               kBicelleBeltRough = 56, kRaspberry = 57, kPearlNecklace = 58, kBinaryHardSphere = 59,
-              kAdsorbedLayer = 60, kPringle = 61, kFlexCylEll = 62 };
+              kAdsorbedLayer = 60, kPringle = 61, kFlexCylEll = 62, kFlexCyl = 63 };
 
 // Randomly oriented lamellae: the weight per unit volume fraction.
 template <int KIND>
@@ -1354,7 +1376,7 @@ __device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, cons
     } else if constexpr (KIND == kScParacrystal || KIND == kBccParacrystal || KIND == kFccParacrystal) {
         const float r = (float)s[0];
         return a.contrast * k43pi * r * r * r * sph3j_d(q * s[0]);
-    } else if constexpr (KIND == kPringle || KIND == kFlexCylEll) {
+    } else if constexpr (KIND == kPringle || KIND == kFlexCylEll || KIND == kFlexCyl) {
         return 0.0f;   // F^2 comes from pringle_f2 / flexcyl_f2
     } else if constexpr (KIND == kSuperball) {
         const float r = (float)s[0];
@@ -1482,7 +1504,7 @@ __device__ __forceinline__ float amplitude_f(const TraceArgs& a, const float s[3
         return (float)kPi * __builtin_fmaf(a.cs_core, core, a.cs_shell * outer);
     } else if constexpr (KIND == kScParacrystal || KIND == kBccParacrystal || KIND == kFccParacrystal) {
         return a.contrast * k43pi * s[0] * s[0] * s[0] * sph3j_f(q * s[0]);
-    } else if constexpr (KIND == kPringle || KIND == kFlexCylEll) {
+    } else if constexpr (KIND == kPringle || KIND == kFlexCylEll || KIND == kFlexCyl) {
         return 0.0f;   // no quadrature mode for these (refused at validation)
     } else if constexpr (KIND == kSuperball) {
         return a.contrast * s[0] * s[0] * s[0] * superball_sum(a, qa * s[0], qb * s[0], qc * s[0]);
@@ -1671,7 +1693,9 @@ __device__ __forceinline__ float quad_average(const TraceArgs& a, const float* _
 // P_cs the average of [2 J1(q r)/(q r)]^2 over the in-plane angle psi,
 // r = R sqrt(sin^2 psi + eps^2 cos^2 psi), by the same rule.  cap_nodes:
 // [t_k, w_k] on [0, 1] (n each), then [sin^2 psi_k, cos^2 psi_k, w_k/...]
-// with the section's weights summing to 1.
+// with the section's weights summing to 1.  ELL false: the circular
+// section, [2 J1(q R)/(q R)]^2 itself (eps = 1, no average).
+template <bool ELL>
 __device__ __forceinline__ float flexcyl_f2(const TraceArgs& a, double Rd, double Ld, double qd)
 {
     const int n = a.cap_n;
@@ -1704,10 +1728,15 @@ __device__ __forceinline__ float flexcyl_f2(const TraceArgs& a, double Rd, doubl
     }
     const float chain = 2.0f / x * (i1 - i2 / x);
     float sec = 0.0f;
-    for (int k = 0; k < n; ++k) {
-        const float r = R * sqrtf(__builtin_fmaf(eps * eps, c2[k], s2[k]));
-        const float l = lambda1_f(q * r);
-        sec = __builtin_fmaf(sw[k], l * l, sec);
+    if constexpr (ELL) {
+        for (int k = 0; k < n; ++k) {
+            const float r = R * sqrtf(__builtin_fmaf(eps * eps, c2[k], s2[k]));
+            const float l = lambda1_f(q * r);
+            sec = __builtin_fmaf(sw[k], l * l, sec);
+        }
+    } else {
+        const float l = lambda1_f(q * R);
+        sec = l * l;
     }
     const float fv = a.contrast * (float)kPi * eps * R * R * L;
     return fv * fv * chain * sec;
@@ -2009,9 +2038,9 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
             f2 = lamellar_f2<KIND>(a, qd);
         } else if constexpr (KIND == kPringle) {
             f2 = pringle_f2(a, (a.poly_mask & 1) ? y : 1.0, (a.poly_mask & 2) ? y : 1.0, qa, qb, qc);
-        } else if constexpr (KIND == kFlexCylEll) {
-            f2 = flexcyl_f2(a, (a.poly_mask & 1) ? a.size[0] * y : a.size[0],
-                            (a.poly_mask & 2) ? a.size[1] * y : a.size[1], qd);
+        } else if constexpr (KIND == kFlexCylEll || KIND == kFlexCyl) {
+            f2 = flexcyl_f2<KIND == kFlexCylEll>(a, (a.poly_mask & 1) ? a.size[0] * y : a.size[0],
+                                                 (a.poly_mask & 2) ? a.size[1] * y : a.size[1], qd);
         } else if constexpr (kSphereFamily<KIND>) {
             f2 = sphere_family_f2<KIND>(a, (a.poly_mask & 1) ? a.size[0] * y : a.size[0], qd);
         } else {

@@ -6,6 +6,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 namespace sans {
@@ -365,6 +369,12 @@ double mean_volume(int kind, const double size[3], double shell, double poly, in
         const int k[3] = {b0 ? 1 : 0, b0 ? 1 : 0, b1 ? 1 : 0};
         return kPiH * extra[1] * expand_moment(f, k, poly_kind, poly);
     }
+    case 63: {
+        // flexible cylinder: pi (R y^b0)^2 (L y^b1)
+        const double f[3][2] = {{size[0], 0.0}, {size[0], 0.0}, {size[1], 0.0}};
+        const int k[3] = {b0 ? 1 : 0, b0 ? 1 : 0, b1 ? 1 : 0};
+        return kPiH * expand_moment(f, k, poly_kind, poly);
+    }
     case 61: {
         // pringle: pi (R y^b0)^2 (t y^b1)
         const double f[3][2] = {{size[0], 0.0}, {size[0], 0.0}, {size[1], 0.0}};
@@ -454,6 +464,262 @@ void cap_rule(bool barbell, double R, double L, double r, int n, float* out)
         out[i] = (float)t;
         out[n + i] = (float)(r * std::sqrt(one_t2));
         out[2 * n + i] = (float)(2.0 * kPiH * r * r * r * one_t2 * gw[i] * 0.5 * (1.0 - t0));
+    }
+}
+
+}  // namespace host
+}  // namespace sans
+
+namespace sans {
+namespace host {
+
+// ------------------------------------------------------------------ MSA
+// Ornstein-Zernike with the mean spherical closure on a radial grid (units
+// of sigma): x_i = i h, h = 1/1024, 0 < i < 65536; gamma = h - c iterated
+// through c = -1 - gamma inside the core, -beta U outside (the mean of the
+// two one-sided values at x = 1), its three-dimensional transform as a sine
+// transform, gamma^ = rho c^2/(1 - rho c^), and back.  The sine transforms
+// by a complex radix-2 FFT of the odd extension (length 2N).
+
+namespace {
+
+constexpr int kMsaIn = 1024;           // grid intervals inside the core
+constexpr int kMsaN = 65536;           // grid points (to x = 64)
+
+// In-place iterative radix-2 FFT (forward, e^{-2 pi i jk/n}), n a power of 2.
+void fft_inplace(std::vector<std::complex<double>>& a, const std::vector<std::complex<double>>& tw)
+{
+    const size_t n = a.size();
+    for (size_t i = 1, j = 0; i < n; ++i) {
+        size_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (size_t len = 2; len <= n; len <<= 1) {
+        const size_t step = n / len;
+        for (size_t i = 0; i < n; i += len)
+            for (size_t k = 0; k < len / 2; ++k) {
+                const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * tw[k * step];
+                a[i + k] = u + v;
+                a[i + k + len / 2] = u - v;
+            }
+    }
+}
+
+// out[j] = sum_{i=1}^{N-1} in[i] sin(pi i j / N), j = 1..N-1 (index j - 1).
+struct Dst {
+    int N;
+    std::vector<std::complex<double>> tw, buf;
+    explicit Dst(int n) : N(n), tw(n), buf(2 * (size_t)n)
+    {
+        for (int k = 0; k < n; ++k) tw[k] = std::polar(1.0, -M_PI * k / n);
+    }
+    void operator()(const std::vector<double>& in, std::vector<double>& out)
+    {
+        const size_t n2 = 2 * (size_t)N;
+        buf[0] = buf[N] = 0.0;
+        for (int i = 1; i < N; ++i) {
+            buf[i] = in[i - 1];
+            buf[n2 - i] = -in[i - 1];
+        }
+        fft_inplace(buf, tw);
+        for (int j = 1; j < N; ++j) out[j - 1] = -0.5 * buf[j].imag();
+    }
+};
+
+bool msa_solve_uncached(double eta, double uc, double ks, double* cin)
+{
+    const int N = kMsaN, M = N - 1;
+    const double h = 1.0 / kMsaIn, L = N * h, rho = 6.0 * eta / M_PI, dk = M_PI / L;
+    std::vector<double> x(M), K(M), u(M);
+    for (int i = 0; i < M; ++i) {
+        x[i] = (i + 1) * h;
+        K[i] = (i + 1) * dk;
+        u[i] = x[i] > 1.0 ? uc * std::exp(-ks * (x[i] - 1.0)) / x[i] : 0.0;
+    }
+    const int i1 = kMsaIn - 1;   // x = 1
+    Dst dst(N);
+    std::vector<double> c(M), t(M), ch(M), gh(M), gn(M);
+    bool physical = true;
+    // one pass gamma -> next gamma at the contact potential us * U_c; clears
+    // `physical` when 1 - rho c^ <= 0 at some K
+    auto step = [&](const std::vector<double>& g, double us, std::vector<double>& res) {
+        for (int i = 0; i < M; ++i) c[i] = x[i] < 1.0 - 0.5 * h ? -1.0 - g[i] : -us * u[i];
+        c[i1] = 0.5 * ((-1.0 - g[i1]) - us * uc);
+        for (int i = 0; i < M; ++i) t[i] = x[i] * c[i];
+        dst(t, ch);
+        physical = true;
+        for (int j = 0; j < M; ++j) {
+            ch[j] *= 4.0 * M_PI * h / K[j];
+            const double d = 1.0 - rho * ch[j];
+            physical = physical && d > 0.0;
+            gh[j] = K[j] * rho * ch[j] * ch[j] / d;
+        }
+        dst(gh, res);
+        for (int i = 0; i < M; ++i) res[i] *= dk / (2.0 * M_PI * M_PI * x[i]);
+    };
+    // Anderson mixing over the last 6 differences (mixing 0.3) at one stage,
+    // from the gamma in g; true once gamma moves by less than tol
+    std::vector<double> f(M);
+    auto anderson = [&](std::vector<double>& g, double us, double tol) {
+        std::vector<std::vector<double>> hg, hf;
+        const int m = 6;
+        const double beta = 0.3;
+        for (int it = 0; it < 400; ++it) {
+            step(g, us, gn);
+            if (!physical) return false;
+            double err = 0.0;
+            for (int i = 0; i < M; ++i) {
+                f[i] = gn[i] - g[i];
+                err = std::max(err, std::fabs(f[i]));
+            }
+            if (!std::isfinite(err)) return false;
+            if (err < tol) {
+                g = gn;
+                return true;
+            }
+            hg.push_back(g);
+            hf.push_back(f);
+            if ((int)hg.size() > m) {
+                hg.erase(hg.begin());
+                hf.erase(hf.begin());
+            }
+            // least squares min |f - dF coef| over the differences of the
+            // history, by modified Gram-Schmidt on the columns of dF (columns
+            // nearly dependent on the earlier ones are dropped)
+            const int nd = (int)hf.size() - 1;
+            std::vector<std::vector<double>> Q;
+            std::vector<int> col;
+            std::vector<double> R((size_t)std::max(nd, 1) * std::max(nd, 1), 0.0);
+            double r00 = 0.0;
+            for (int a = 0; a < nd; ++a) {
+                std::vector<double> v(M);
+                for (int i = 0; i < M; ++i) v[i] = hf[a + 1][i] - hf[a][i];
+                double n0 = 0.0;
+                for (int i = 0; i < M; ++i) n0 += v[i] * v[i];
+                r00 = std::max(r00, std::sqrt(n0));
+                for (size_t b = 0; b < Q.size(); ++b) {
+                    double d = 0.0;
+                    for (int i = 0; i < M; ++i) d += Q[b][i] * v[i];
+                    R[b * nd + a] = d;
+                    for (int i = 0; i < M; ++i) v[i] -= d * Q[b][i];
+                }
+                double nv = 0.0;
+                for (int i = 0; i < M; ++i) nv += v[i] * v[i];
+                nv = std::sqrt(nv);
+                if (!(nv > 1e-12 * r00)) continue;
+                for (int i = 0; i < M; ++i) v[i] /= nv;
+                R[Q.size() * nd + a] = nv;
+                Q.push_back(std::move(v));
+                col.push_back(a);
+            }
+            const int nk = (int)Q.size();
+            std::vector<double> coef(std::max(nd, 1), 0.0);
+            for (int b = 0; b < nk; ++b) {
+                double d = 0.0;
+                for (int i = 0; i < M; ++i) d += Q[b][i] * f[i];
+                coef[col[b]] = d;
+            }
+            // R restricted to the kept columns is upper triangular
+            for (int b = nk - 1; b >= 0; --b) {
+                double v = coef[col[b]];
+                for (int c2 = b + 1; c2 < nk; ++c2) v -= R[b * nd + col[c2]] * coef[col[c2]];
+                coef[col[b]] = v / R[b * nd + col[b]];
+            }
+            for (int i = 0; i < M; ++i) {
+                double v = g[i] + beta * f[i];
+                for (int a = 0; a < nd; ++a)
+                    v -= ((hg[a + 1][i] - hg[a][i]) + beta * (hf[a + 1][i] - hf[a][i])) * coef[a];
+                g[i] = v;
+            }
+        }
+        return false;
+    };
+    // continuation in the contact potential from the uncharged spheres:
+    // stages U_c s / S, S = max(1, ceil U_c), to 1e-8 on the way and 1e-12
+    // at the end
+    std::vector<double> g(M, 0.0);
+    const int stages = std::max(1, (int)std::ceil(uc));
+    for (int s = 1; s <= stages; ++s)
+        if (!anderson(g, (double)s / stages, s == stages ? 1e-12 : 1e-8)) return false;
+    step(g, 1.0, gn);                 // c^ of the solution
+    if (!physical) return false;
+    // gamma(0) from its transform, the inside c on x = i/1024
+    double g0 = 0.0;
+    for (int j = 0; j < M; ++j) g0 += K[j] * gh[j];
+    g0 *= dk / (2.0 * M_PI * M_PI);
+    cin[0] = -1.0 - g0;
+    for (int i = 1; i <= kMsaIn; ++i) cin[i] = -1.0 - g[i - 1];
+    return true;
+}
+
+}  // namespace
+
+bool msa_solve(double eta, double uc, double ks, double* cin)
+{
+    // solutions by (eta, U_c, kappa sigma): one solve serves every model
+    // and experiment that shares them (at most 64 kept, then all dropped)
+    static std::mutex mu;
+    static std::map<std::tuple<double, double, double>, std::vector<double>> cache;
+    const auto key = std::make_tuple(eta, uc, ks);
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            if (it->second.empty()) return false;
+            std::copy(it->second.begin(), it->second.end(), cin);
+            return true;
+        }
+    }
+    std::vector<double> v(kMsaIn + 1);
+    const bool ok = msa_solve_uncached(eta, uc, ks, v.data());
+    std::lock_guard<std::mutex> lock(mu);
+    if (cache.size() >= 64) cache.clear();
+    if (ok) {
+        std::copy(v.begin(), v.end(), cin);
+        cache[key] = std::move(v);
+    } else {
+        cache[key] = std::vector<double>();
+    }
+    return ok;
+}
+
+void msa_knots(const double* cin, double eta, double uc, double ks, double kmax, int n, float* out)
+{
+    // c^(K) = 4 pi / K int_0^1 x c(x) sin(K x) dx (Simpson) + the tail's
+    // closed form T(K) = -4 pi U_c N / D, N = ks sin K + K cos K,
+    // D = K (ks^2 + K^2); S = 1 / (1 - rho c^), S' = rho S^2 c^'
+    const double h = 1.0 / kMsaIn, rho = 6.0 * eta / M_PI, dK = kmax / (n - 1);
+    std::vector<double> wxc(kMsaIn + 1);
+    for (int i = 0; i <= kMsaIn; ++i) {
+        const double w = (i == 0 || i == kMsaIn) ? 1.0 : (i % 2 ? 4.0 : 2.0);
+        wxc[i] = w * h / 3.0 * (i * h) * cin[i];
+    }
+    for (int j = 0; j < n; ++j) {
+        const double Kq = dK * j;
+        double ch, dch;
+        if (j == 0) {
+            double m2 = 0.0;
+            for (int i = 0; i <= kMsaIn; ++i) m2 += wxc[i] * (i * h);
+            ch = 4.0 * M_PI * m2 - 4.0 * M_PI * uc * (1.0 / ks + 1.0 / (ks * ks));
+            dch = 0.0;                 // c^ is even in K
+        } else {
+            double I = 0.0, J = 0.0;
+            for (int i = 0; i <= kMsaIn; ++i) {
+                const double xi = i * h;
+                I += wxc[i] * std::sin(Kq * xi);
+                J += wxc[i] * xi * std::cos(Kq * xi);
+            }
+            const double sK = std::sin(Kq), cK = std::cos(Kq);
+            const double N = ks * sK + Kq * cK, dN = (ks + 1.0) * cK - Kq * sK;
+            const double D = Kq * (ks * ks + Kq * Kq), dD = ks * ks + 3.0 * Kq * Kq;
+            ch = 4.0 * M_PI * I / Kq - 4.0 * M_PI * uc * N / D;
+            dch = 4.0 * M_PI * (J / Kq - I / (Kq * Kq)) - 4.0 * M_PI * uc * (dN * D - N * dD) / (D * D);
+        }
+        const double S = 1.0 / (1.0 - rho * ch);
+        out[2 * j] = (float)S;
+        out[2 * j + 1] = (float)(dK * rho * S * S * dch);
     }
 }
 

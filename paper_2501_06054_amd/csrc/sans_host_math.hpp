@@ -34,6 +34,18 @@ void cap_rule(bool barbell, double R, double L, double r, int n, float* out);
 void superball_rule(double p, int n, float* out);
 inline int superball_rule_size(int n) { return n + 3 * n * n; }
 double superball_volume(double R, double p);
+// Hayter-Penfold structure factor: hard spheres of diameter sigma with
+// beta U = uc (sigma/r) exp(-ks (r/sigma - 1)) outside the core, in the mean
+// spherical approximation.  msa_solve: the direct correlation c(x) inside
+// the core at x = i/1024, i = 0..1024 (cin, 1025 values; x in units of
+// sigma); false when the iteration does not reach a physical solution
+// (1 - rho c^ > 0 everywhere).  Solutions are cached by (eta, uc, ks).
+constexpr int kMsaCin = 1025;
+bool msa_solve(double eta, double uc, double ks, double* cin);
+// S(K) and dK S'(K) at the n knots K_j = j dK, dK = kmax/(n - 1)
+// (K = q sigma), interleaved (out: 2n floats), for cubic Hermite
+// interpolation.
+void msa_knots(const double* cin, double eta, double uc, double ks, double kmax, int n, float* out);
 
 }  // namespace host
 }  // namespace sans

@@ -27,7 +27,7 @@ namespace sans {
 
 constexpr int kBlock = 256;
 constexpr int kXcds = 8;
-constexpr int kNumKinds = 63;
+constexpr int kNumKinds = 64;
 constexpr int kKindGroups = 8;
 
 // ------------------------------------------------------------------ kernels

@@ -401,17 +401,38 @@ size_t rule_floats(const sans_params& p)
     if (p.kind == SANS_BINARY_HARD_SPHERE) return 4 * 32;
     if (p.kind == SANS_PRINGLE) return 8 * (size_t)p.quad_n * p.quad_n;
     if (p.kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL) return 5 * (size_t)p.quad_n;
+    if (p.kind == SANS_FLEXIBLE_CYLINDER) return 2 * (size_t)p.quad_n;
     if (p.kind == SANS_POLYMER_EXCL_VOLUME) return 4 * (size_t)kPevRuleNodes;
     return 0;
 }
 
-// The rule, then the constants of an adhesive or square-well structure factor.
+// The Hayter-Penfold table spans K = q sigma from 0 to 1.01 sigma q_max (the
+// largest q of the cone) with knots at most 0.01 apart (256 to 65536 knots).
+double msa_kmax(const sans_params& p)
+{
+    const double lmin = p.lambda0 * (1.0 - p.dlambda_rel);
+    return 2.0 * p.sq_radius * 4.0 * kPi / lmin * std::sin(0.5 * p.cone_alpha) * 1.01;
+}
+int msa_knot_count(const sans_params& p)
+{
+    const double n = std::ceil(msa_kmax(p) / 0.01) + 1.0;
+    return (int)std::min(65536.0, std::max(256.0, n));
+}
+
+// The rule, then the constants of an adhesive or square-well structure
+// factor, or the Hayter-Penfold knots.
 bool needs_sq_coef(const sans_params& p) { return p.sq_phi > 0.0 && p.sq_kind != SANS_SQ_HARD_SPHERE; }
-size_t node_floats(const sans_params& p) { return rule_floats(p) + (needs_sq_coef(p) ? kSqCoef : 0); }
+size_t sq_floats(const sans_params& p)
+{
+    if (!needs_sq_coef(p)) return 0;
+    return p.sq_kind == SANS_SQ_HAYTER_MSA ? kMsaHead + 2 * (size_t)msa_knot_count(p) : (size_t)kSqCoef;
+}
+size_t node_floats(const sans_params& p) { return rule_floats(p) + sq_floats(p); }
 
 // Fills the node buffer of one parameter set (node_floats(p) floats) and
-// points the kernel arguments at it (base: its device address).
-void fill_nodes(const sans_params& p, float* out, const float* base, TraceArgs& a)
+// points the kernel arguments at it (base: its device address).  False
+// when the Hayter-Penfold solve (done first in validation) fails.
+bool fill_nodes(const sans_params& p, float* out, const float* base, TraceArgs& a)
 {
     const size_t nr = rule_floats(p);
     if (p.kind == SANS_SUPERBALL) {
@@ -434,16 +455,19 @@ void fill_nodes(const sans_params& p, float* out, const float* base, TraceArgs& 
                 out[2 * h * n + k] = (float)std::pow(w, 6.0);
                 out[(2 * h + 1) * n + k] = (float)(6.0 * 0.5 * gw[k] * std::pow(w, 6.0 * sv[h] - 1.0));
             }
-    } else if (p.kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL) {
-        // the chain's rule on [0, 1] (scaled to [0, x_e] per event) and the
-        // section's angle psi in [0, pi/2] (weights of the average, sum 1)
+    } else if (p.kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL || p.kind == SANS_FLEXIBLE_CYLINDER) {
+        // the chain's rule on [0, 1] (scaled to [0, x_e] per event) and, for
+        // the ellipse, the section's angle psi in [0, pi/2] (weights of the
+        // average, sum 1)
         const int n = p.quad_n;
+        const bool ell = p.kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL;
         std::vector<double> gx(n), gw(n);
         host::gauss_legendre(n, gx.data(), gw.data());
         for (int k = 0; k < n; ++k) {
-            const double psi = 0.25 * kPi * (gx[k] + 1.0);
             out[k] = (float)(0.5 * (gx[k] + 1.0));
             out[n + k] = (float)(0.5 * gw[k]);
+            if (!ell) continue;
+            const double psi = 0.25 * kPi * (gx[k] + 1.0);
             out[2 * n + k] = (float)(std::sin(psi) * std::sin(psi));
             out[3 * n + k] = (float)(std::cos(psi) * std::cos(psi));
             out[4 * n + k] = (float)(0.5 * gw[k]);
@@ -506,8 +530,22 @@ void fill_nodes(const sans_params& p, float* out, const float* base, TraceArgs& 
         host::cap_rule(p.kind == SANS_BARBELL, p.size[0], p.size[1], p.size[2], p.quad_n, out);
     }
     if (nr) a.cap_nodes = base;
-    if (!needs_sq_coef(p)) return;
+    if (!needs_sq_coef(p)) return true;
     float* c = out + nr;
+    a.sq_coef = base + nr;
+    if (p.sq_kind == SANS_SQ_HAYTER_MSA) {
+        // head: 1/dK, n - 1; then (S, dK S') at K_j = j dK (the solve is
+        // cached from validation)
+        const int n = msa_knot_count(p);
+        const double kmax = msa_kmax(p);
+        std::vector<double> cin(host::kMsaCin);
+        if (!host::msa_solve(p.sq_phi, p.sq_extra[0], p.sq_extra[1], cin.data())) return false;
+        for (int k = 0; k < kMsaHead; ++k) c[k] = 0.0f;
+        c[0] = (float)((n - 1) / kmax);
+        c[1] = (float)(n - 1);
+        host::msa_knots(cin.data(), p.sq_phi, p.sq_extra[0], p.sq_extra[1], kmax, n, c + kMsaHead);
+        return true;
+    }
     for (int k = 0; k < kSqCoef; ++k) c[k] = 0.0f;
     if (p.sq_kind == SANS_SQ_STICKY_HARD_SPHERE) {
         double ca[kPySeriesTerms], cb[kPySeriesTerms], hbc[3];
@@ -526,14 +564,14 @@ void fill_nodes(const sans_params& p, float* out, const float* base, TraceArgs& 
         c[kSqW] = (float)w;
         c[kSqW3] = (float)(w * w * w);
     }
-    a.sq_coef = base + nr;
+    return true;
 }
 
 int validate(const sans_params* p)
 {
     if (!p) return fail(SANS_E_INVALID_ARG, "params is NULL");
     if (p->abi_version != SANS_ABI_VERSION) return fail(SANS_E_INVALID_ARG, "abi_version mismatch");
-    if (p->kind < 0 || p->kind > 62) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
+    if (!known_kind(p->kind)) return fail(SANS_E_UNSUPPORTED, "unknown model kind");
     if (p->mode < 0 || p->mode > 2) return fail(SANS_E_UNSUPPORTED, "unknown mode");
     if (p->mode == SANS_MODE_SURROGATE) {
         if (p->kind != SANS_ELLIPSOID && p->kind != SANS_PARALLELEPIPED)
@@ -554,7 +592,7 @@ int validate(const sans_params* p)
                            || p->kind == SANS_LAMELLAR_HG || p->kind == SANS_LAMELLAR_STACK_CAILLE
                            || p->kind == SANS_LAMELLAR_STACK_PARACRYSTAL
                            || p->kind == SANS_CORE_SHELL_BICELLE_ELLIPTICAL_BELT_ROUGH || p->kind == SANS_PRINGLE
-                           || p->kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL;
+                           || p->kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL || p->kind == SANS_FLEXIBLE_CYLINDER;
     int nsize = (p->kind <= 1 || p->kind == SANS_SUPERBALL || p->kind == SANS_ADSORBED_LAYER) ? 1 : (two_sizes ? 2 : 3);
     if (is_shape_independent(p->kind))
         nsize = (p->kind == SANS_POWER_LAW || p->kind == SANS_GAUSSIAN_PEAK || p->kind == SANS_LORENTZ_PEAK
@@ -586,9 +624,11 @@ int validate(const sans_params* p)
         if (p->poly > 0.0 && (p->poly_mask & 4))
             return fail(SANS_E_UNSUPPORTED, "pringle: poly_mask bits 0 (radius) and 1 (thickness) only");
     }
-    if (p->kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL) {
-        if (!(p->extra[0] > 0.0 && finite(p->extra[0]) && p->extra[1] > 0.0 && finite(p->extra[1])))
-            return fail(SANS_E_INVALID_ARG, "flexible cylinder: Kuhn length extra[0] and axis ratio extra[1] must be > 0");
+    if (p->kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL || p->kind == SANS_FLEXIBLE_CYLINDER) {
+        if (!(p->extra[0] > 0.0 && finite(p->extra[0])))
+            return fail(SANS_E_INVALID_ARG, "flexible cylinder: Kuhn length extra[0] must be > 0");
+        if (p->kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL && !(p->extra[1] > 0.0 && finite(p->extra[1])))
+            return fail(SANS_E_INVALID_ARG, "flexible elliptical cylinder: axis ratio extra[1] must be > 0");
         if (p->quad_n < 1 || p->quad_n > kMaxQuad) return fail(SANS_E_INVALID_ARG, "quad_n must be in 1..256");
         if (p->mode != SANS_MODE_MC) return fail(SANS_E_UNSUPPORTED, "flexible cylinder: Monte Carlo mode only");
         if (p->poly > 0.0 && (p->poly_mask & 4))
@@ -770,8 +810,20 @@ int validate(const sans_params* p)
     if (p->mu_att > 0.0 && p->mode == SANS_MODE_SURROGATE)
         return fail(SANS_E_UNSUPPORTED, "surrogate mode: no attenuation");
     if (p->sq_phi > 0.0 && !(p->sq_radius > 0.0)) return fail(SANS_E_INVALID_ARG, "sq_radius must be > 0");
-    if (p->sq_kind < SANS_SQ_HARD_SPHERE || p->sq_kind > SANS_SQ_SQUARE_WELL)
+    if (p->sq_kind < SANS_SQ_HARD_SPHERE || p->sq_kind > SANS_SQ_HAYTER_MSA)
         return fail(SANS_E_UNSUPPORTED, "unknown sq_kind");
+    if (p->sq_phi > 0.0 && p->sq_kind == SANS_SQ_HAYTER_MSA) {
+        if (!(p->sq_extra[0] >= 0.0 && p->sq_extra[0] <= 50.0))
+            return fail(SANS_E_INVALID_ARG, "Hayter-Penfold: contact potential sq_extra[0] must be in [0, 50]");
+        if (!(p->sq_extra[1] > 0.0 && p->sq_extra[1] <= 50.0))
+            return fail(SANS_E_INVALID_ARG, "Hayter-Penfold: screening sq_extra[1] must be in (0, 50]");
+        if (!(p->lambda0 > 0.0 && p->dlambda_rel >= 0.0 && p->dlambda_rel < 1.0 && p->cone_alpha > 0.0
+              && std::isfinite(msa_kmax(*p))))
+            return fail(SANS_E_INVALID_ARG, "Hayter-Penfold: the instrument's q range is not finite");
+        std::vector<double> cin(host::kMsaCin);
+        if (!host::msa_solve(p->sq_phi, p->sq_extra[0], p->sq_extra[1], cin.data()))
+            return fail(SANS_E_DOMAIN, "Hayter-Penfold: no physical solution at these parameters");
+    }
     if (p->sq_phi > 0.0 && p->sq_kind == SANS_SQ_STICKY_HARD_SPHERE) {
         if (!(p->sq_extra[0] > 0.0 && finite(p->sq_extra[0])))
             return fail(SANS_E_INVALID_ARG, "adhesive spheres: stickiness sq_extra[0] must be > 0");
@@ -1156,10 +1208,10 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     }
     if (p->kind == SANS_SUPERBALL) a.cap_n = p->quad_n;
     if (p->kind == SANS_PRINGLE) a.cap_n = p->quad_n;
-    if (p->kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL) {
+    if (p->kind == SANS_FLEXIBLE_CYLINDER_ELLIPTICAL || p->kind == SANS_FLEXIBLE_CYLINDER) {
         a.cap_n = p->quad_n;
         a.fc_b = (float)p->extra[0];
-        a.fc_eps = (float)p->extra[1];
+        a.fc_eps = p->kind == SANS_FLEXIBLE_CYLINDER ? 1.0f : (float)p->extra[1];
     }
     if (p->kind == SANS_ADSORBED_LAYER) {
         a.lam_c = (float)(6.0 * kPi / p->size[0]);
@@ -1295,13 +1347,15 @@ int configure(sans_model_s* m, const sans_params* p)
     }
 
     // the end caps' rule or the superball's nested rule (every mode), then the
-    // constants of an adhesive or square-well structure factor
+    // constants of an adhesive or square-well structure factor or the
+    // Hayter-Penfold knots
     if (node_floats(*p)) {
         std::vector<float> rule(node_floats(*p));
         if (m->d_caps) HIP_TRY(hipFree(m->d_caps));
         m->d_caps = nullptr;
         HIP_TRY(hipMalloc(&m->d_caps, sizeof(float) * rule.size()));
-        fill_nodes(*p, rule.data(), m->d_caps, a);
+        if (!fill_nodes(*p, rule.data(), m->d_caps, a))
+            return fail(SANS_E_DOMAIN, "Hayter-Penfold: no physical solution at these parameters");
         HIP_TRY(hipMemcpy(m->d_caps, rule.data(), sizeof(float) * rule.size(), hipMemcpyHostToDevice));
     }
 
@@ -2158,6 +2212,7 @@ double model_cost(const sans_params& p)
     case SANS_SUPERBALL: return 1.0 + (19.0 * n + 38.0 * n * n) / 900.0;
     case SANS_PRINGLE: return 1.0 + 36.0 * 2.0 * n * n / 900.0;
     case SANS_FLEXIBLE_CYLINDER_ELLIPTICAL: return 0.7 + 40.0 * n / 900.0;
+    case SANS_FLEXIBLE_CYLINDER: return 0.7 + 28.0 * n / 900.0;
     case SANS_PEARL_NECKLACE: return 1.0 + (55.0 * n + 8.0 * p.extra[0]) / 900.0;
     case SANS_LAMELLAR_STACK_CAILLE:
     case SANS_LAMELLAR_HG_STACK_CAILLE:
@@ -2382,7 +2437,8 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
         if (node_floats(p[e])) {
             const size_t off = host_caps.size();
             host_caps.resize(off + node_floats(p[e]));
-            fill_nodes(p[e], host_caps.data() + off, c.d_caps + off, exps[e]);
+            if (!fill_nodes(p[e], host_caps.data() + off, c.d_caps + off, exps[e]))
+                return fail(SANS_E_DOMAIN, "Hayter-Penfold: no physical solution at these parameters");
         }
     }
     if (!host_caps.empty())

@@ -49,7 +49,7 @@ POLY_KINDS = ("schulz", "gaussian")
 #: structure factors (when sq_phi > 0): Percus-Yevick hard spheres, Baxter's
 #: adhesive hard spheres (sq_extra[0] = stickiness), square-well fluid in the
 #: mean spherical approximation (sq_extra = depth in kT, width in diameters)
-SQ_KINDS = ("hard_sphere", "sticky_hard_sphere", "square_well")
+SQ_KINDS = ("hard_sphere", "sticky_hard_sphere", "square_well", "hayter_msa")
 
 DEG = math.pi / 180.0
 
@@ -446,6 +446,26 @@ def flexible_cylinder_elliptical() -> dict:
                               phi=0.01, extra=(100.0, 1.5, 0, 0), quad_n=48, nx=256, ny=256))
 
 
+def flexible_cylinder() -> dict:
+    """Flexible cylinders with a circular cross-section: contour length 1000
+    A, Kuhn length 100 A, radius 20 A (Schulz, sigma/mean 0.1), the chain
+    integrals by a 48-point rule, 256x256, 1e8 neutrons."""
+    return dict(name="flexible_cylinder", n=10**8, seed=35, exp_id=0,
+                params=params(kind="flexible_cylinder", size=(20.0, 1000.0, 0), sld=(1e-6, 0, 0),
+                              phi=0.01, extra=(100.0, 0, 0, 0), quad_n=48, poly=0.1, poly_mask=1,
+                              nx=256, ny=256))
+
+
+def charged_spheres() -> dict:
+    """Charged spheres (Schulz radius 45 A, sigma/mean 0.1) at volume fraction
+    0.12 with the Hayter-Penfold S(Q) of radius 45 A: contact potential 6 kT,
+    screening kappa sigma = 1.8; 256x256, 1e8 neutrons."""
+    return dict(name="charged_spheres", n=10**8, seed=34, exp_id=0,
+                params=params(kind="sphere", size=(45.0, 0, 0), sld=(1e-6, 0, 6.3e-6), phi=0.12, poly=0.1,
+                              sq_phi=0.12, sq_radius=45.0, sq_kind="hayter_msa", sq_extra=(6.0, 1.8),
+                              nx=256, ny=256))
+
+
 WORKLOADS = {
     "tiny_sphere": tiny_sphere,
     "coreshell_py": coreshell_py,
@@ -483,6 +503,8 @@ WORKLOADS = {
     "poly_sep_cylinder": poly_sep_cylinder,
     "flexible_cylinder_elliptical": flexible_cylinder_elliptical,
     "poly_sep_parallelepiped": poly_sep_parallelepiped,
+    "charged_spheres": charged_spheres,
+    "flexible_cylinder": flexible_cylinder,
 }
 
 

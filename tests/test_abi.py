@@ -176,6 +176,15 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
     # a deep, wide well drives 1/S(0) below zero
     (dict(kind="sphere", sq_phi=0.2, sq_radius=50.0, sq_kind="square_well", sq_extra=(3.0, 2.0)),
      "SANS_E_DOMAIN"),
+    (dict(kind="flexible_cylinder", size=(10.0, 500.0, 0.0), extra=(0.0, 0, 0, 0)), "SANS_E_INVALID_ARG"),
+    (dict(kind="flexible_cylinder", size=(10.0, 500.0, 0.0), extra=(50.0, 0, 0, 0), mode="quad",
+          orient_kind="isotropic"), "SANS_E_UNSUPPORTED"),
+    (dict(kind="sphere", sq_phi=0.1, sq_radius=50.0, sq_kind="hayter_msa", sq_extra=(-1.0, 2.0)),
+     "SANS_E_INVALID_ARG"),
+    (dict(kind="sphere", sq_phi=0.1, sq_radius=50.0, sq_kind="hayter_msa", sq_extra=(60.0, 2.0)),
+     "SANS_E_INVALID_ARG"),
+    (dict(kind="sphere", sq_phi=0.1, sq_radius=50.0, sq_kind="hayter_msa", sq_extra=(3.0, 0.0)),
+     "SANS_E_INVALID_ARG"),
     (dict(kind="superball", size=(30.0, 0.0, 0.0), extra=(0.2, 0, 0, 0)), "SANS_E_INVALID_ARG"),
     (dict(kind="superball", size=(30.0, 0.0, 0.0), extra=(2.0, 0, 0, 0), quad_n=0), "SANS_E_INVALID_ARG"),
     (dict(kind="superball", size=(30.0, 0.0, 0.0), extra=(2.0, 0, 0, 0), mode="quad", orient_kind="isotropic"),
@@ -232,6 +241,6 @@ def test_unknown_kind_rejected_without_gpu(S):
 def test_unknown_structure_factor_rejected_without_gpu(S):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(kind="sphere", sq_phi=0.1, sq_radius=50.0))
-    sp.sq_kind = 3
+    sp.sq_kind = max(S.SQ_KIND.values()) + 1
     h = C.c_void_p()
     assert S.lib.sans_model_create(C.byref(sp), C.byref(h)) == S.SANS_E_UNSUPPORTED

@@ -192,7 +192,7 @@ def test_batch_extra_models(S):
     hollow and core-shell bodies, polymer micelles and shape-independent
     models mixed with the other models: each equals its plain trace, and the
     extra models match the oracle."""
-    exps = _small_batch(n_exp=40, n_lo=2e5, n_hi=5e5)
+    exps = _small_batch(n_exp=42, n_lo=2e5, n_hi=5e5)
     caps = {1: dict(kind="barbell", size=(20.0, 300.0, 35.0), poly_mask=7, quad_n=40),
             4: dict(kind="capped_cylinder", size=(30.0, 120.0, 45.0), poly=0.1, poly_mask=7, quad_n=23),
             7: dict(kind="barbell", size=(15.0, 80.0, 15.0), poly_mask=7, quad_n=76),
@@ -250,7 +250,11 @@ def test_batch_extra_models(S):
                      extra=(0.08, 0, 0, 0), poly=0.0, sq_phi=0.0),
             38: dict(kind="adsorbed_layer", size=(1500.0, 0.0, 0.0), shell=2.0, sld=(1.5e-6, 0.0, 6.3e-6),
                      extra=(10.0, 0, 0, 0), poly=0.0, sq_phi=0.0),
-            39: dict(kind="pringle", size=(40.0, 8.0, 0.0), extra=(0.002, 0.015, 0, 0), quad_n=10, poly_mask=3)}
+            39: dict(kind="pringle", size=(40.0, 8.0, 0.0), extra=(0.002, 0.015, 0, 0), quad_n=10, poly_mask=3),
+            40: dict(kind="sphere", size=(40.0, 0.0, 0.0), poly_mask=1, sq_phi=0.12, sq_radius=44.0,
+                     sq_kind="hayter_msa", sq_extra=(6.0, 1.8)),
+            41: dict(kind="flexible_cylinder", size=(15.0, 800.0, 0.0), extra=(80.0, 0, 0, 0), quad_n=24,
+                     poly_mask=3)}
     for e, over in caps.items():
         exps[e]["params"] = dict(exps[e]["params"], **over)
     got = _run_batch(S, exps)
@@ -259,7 +263,7 @@ def test_batch_extra_models(S):
         ref = m.trace(x["n"], x["seed"], exp_id=e).cpu().numpy()
         m.close()
         assert np.allclose(got[e], ref, rtol=SAME_EXPERIMENT_RTOL, atol=0), e
-    for e in (1, 4, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 32, 33, 34, 35, 36, 37, 38, 39):
+    for e in (1, 4, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 32, 33, 34, 35, 36, 37, 38, 39, 40, 41):
         x = exps[e]
         ref = oracle.trace(x["params"], x["n"], x["seed"], exp_id=e, nthreads=NTHREADS)
         assert np.array_equal(got[e] != 0, ref != 0), e

@@ -312,10 +312,24 @@ PER_NEUTRON = {
     "flexcyl_flexible_flat": (W.params(kind="flexible_cylinder_elliptical", size=(10.0, 3000.0, 0),
                                        extra=(40.0, 3.0, 0, 0), quad_n=64, poly=0.15, poly_mask=1,
                                        poly_kind="gaussian"), 20011),
+    "flexible_cylinder": (W.workload("flexible_cylinder")["params"], 20011),
+    "flexcyl_round_long_len_poly": (W.params(kind="flexible_cylinder", size=(8.0, 4000.0, 0),
+                                             extra=(60.0, 0, 0, 0), quad_n=64, poly=0.2, poly_mask=2,
+                                             poly_kind="gaussian"), 20011),
     # sample attenuation
     "attenuated_coreshell": (dict(W.workload("coreshell_py")["params"], mu_att=150.0), 30011),
     "attenuated_wide_cone_cylinder": (W.params(kind="cylinder", size=(20.0, 200.0, 0), orient_kind="isotropic",
                                                cone_alpha=1.0, sample_d=0.003, mu_att=400.0), 30011),
+    # Hayter-Penfold charged spheres (the Ornstein-Zernike solve at set-up,
+    # S tabulated over the instrument's q range)
+    "charged_spheres": (W.workload("charged_spheres")["params"], 30011),
+    "hayter_strong_cylinder": (W.params(kind="cylinder", size=(20.0, 90.0, 0), orient_kind="isotropic",
+                                        sq_phi=0.3, sq_radius=30.0, sq_kind="hayter_msa", sq_extra=(20.0, 3.0)),
+                               20011),
+    "hayter_weak_screening_poly": (W.params(kind="core_shell", size=(40.0, 0, 0), shell=8.0,
+                                            sld=(1e-6, 3e-6, 6.3e-6), phi=0.05, poly=0.15, poly_mask=1,
+                                            sq_phi=0.05, sq_radius=48.0, sq_kind="hayter_msa",
+                                            sq_extra=(3.0, 0.4)), 20011),
     # pringle (complex amplitude, a polar rule per event)
     "pringle_iso": (W.params(kind="pringle", size=(60.0, 10.0, 0), extra=(0.001, 0.02, 0, 0), quad_n=16,
                              orient_kind="isotropic"), 10011),
@@ -356,7 +370,7 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "belt_bicelle_gauss", "raspberry_poly", "pearl_necklace", "binary_hard_sphere",
              "adsorbed_layer", "pringle_iso", "attenuated_coreshell", "poly_sep_cylinder",
              "poly_sep_parallelepiped", "poly_sep_ellipsoid_gauss", "flexible_cylinder_elliptical",
-             "flexcyl_flexible_flat"]
+             "flexcyl_flexible_flat", "charged_spheres", "hayter_strong_cylinder", "flexible_cylinder"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -371,6 +385,27 @@ def test_detector_parity(S, name, tally):
     ref, bar = oracle_detector(p, n, seed)
     check_detector(det.cpu().numpy(), ref, f"{name}/{tally}", **bar)
     m.close()
+
+
+def test_uncharged_hayter_penfold_is_percus_yevick(S):
+    """With no charge (U_c = 0) the mean spherical approximation of charged
+    hard spheres is the Percus-Yevick closure: the detector of the Hayter-
+    Penfold table equals that of the closed-form hard-sphere S(Q) to FP32
+    rounding of the weights."""
+    base = W.params(kind="sphere", size=(40.0, 0, 0), sld=(1e-6, 0, 6.3e-6), phi=0.25, poly=0.1,
+                    sq_phi=0.25, sq_radius=40.0, nx=128, ny=128)
+    n, seed = 300_007, 8
+    log(f"uncharged Hayter-Penfold vs Percus-Yevick n={n}")
+    dets = []
+    for over in (dict(sq_kind="hard_sphere"), dict(sq_kind="hayter_msa", sq_extra=(0.0, 1.0))):
+        m = S.Model(dict(base, **over))
+        dets.append(m.trace(n, seed).cpu().numpy())
+        m.close()
+    hs, msa = dets
+    assert np.array_equal(hs != 0, msa != 0)
+    nz = hs != 0
+    assert np.max(np.abs(msa[nz] - hs[nz]) / hs[nz]) < 2e-5
+    assert abs(msa.sum() - hs.sum()) <= 2e-6 * hs.sum()
 
 
 @pytest.mark.parametrize("name", ["quad_parallelepiped", "quad_capped_cylinder", "quad_hollow_prism",

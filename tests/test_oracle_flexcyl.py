@@ -13,6 +13,9 @@ cross-section, both by the model's own Gauss-Legendre rule).
   the elliptical average against SciPy's adaptive quadrature of the angle
   integral; eps and 1/eps with R scaled give the same ellipse.
 - The rule: 48 points against 256 on the workload's parameters.
+- The plain flexible cylinder (circular section): the elliptical one at
+  eps = 1, the chain times SciPy's [2 J1(qR)/(qR)]^2, forward value and
+  mean volume.
 - F^2(q -> 0) = (drho pi eps R^2 L)^2 and <V> = pi eps R^2 L (moments of the
   size draw for the mask's sizes).
 """
@@ -92,3 +95,27 @@ def test_forward_value_and_volume():
     a = 1 / 0.2**2
     m3 = (a + 1) * (a + 2) / a**2      # <y^3> of the Schulz draw: R^2 L scale together
     assert oracle.mean_volume(pp) == pytest.approx(v * m3, rel=1e-12)
+
+
+def test_round_section_is_the_ellipse_at_axis_ratio_one():
+    """The plain flexible cylinder (circular section) is the elliptical one at
+    eps = 1, whose section average reduces to [2 J1(qR)/(qR)]^2 (pinned above
+    against SciPy's J1); the forward value is (drho pi R^2 L)^2 and the mean
+    volume pi R^2 L with the size moments of the draw."""
+    base = dict(W.workload("flexible_cylinder_elliptical")["params"], quad_n=40)
+    round_ = dict(base, kind="flexible_cylinder", extra=(base["extra"][0], 0.0, 0, 0))
+    ell = dict(base, extra=(base["extra"][0], 1.0, 0, 0))
+    R, L, b = base["size"][0], base["size"][1], base["extra"][0]
+    for q in np.geomspace(1e-4, 0.3, 30):
+        got = oracle.form_f2(round_, q, (q, 0.0, 0.0))
+        assert got == pytest.approx(oracle.form_f2(ell, q, (q, 0.0, 0.0)), rel=1e-12)
+        lam = (2 * special.j1(q * R) / (q * R)) ** 2
+        v = (base["sld"][0] - base["sld"][2]) * math.pi * R * R * L
+        assert got == pytest.approx(v * v * oracle.flexcyl_chain(q, L, b, 40) * lam, rel=1e-12)
+    assert oracle.form_f2(round_, 1e-8, (1e-8, 0, 0)) == pytest.approx(
+        ((base["sld"][0] - base["sld"][2]) * math.pi * R * R * L) ** 2, rel=1e-6)
+    for mask, k in ((1, 2), (2, 1), (3, 3)):
+        pp = dict(round_, poly=0.2, poly_mask=mask)
+        a = 1 / 0.2**2
+        mk = {1: 1.0, 2: (a + 1) / a, 3: (a + 1) * (a + 2) / a**2}[k]     # <y^k> of the Schulz draw
+        assert oracle.mean_volume(pp) == pytest.approx(math.pi * R * R * L * mk, rel=1e-12)
