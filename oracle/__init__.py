@@ -184,6 +184,10 @@ def lib():
         L.orc_surrogate_judge.restype = i32
         L.orc_trace_debug_ex.argtypes = [P(OrcParams), u64, u64, u64, u32, P(d)]
         L.orc_trace_debug_ex.restype = i32
+        L.orc_transmitted_debug.argtypes = [P(OrcParams), u64, u64, u64, u32, P(i32), P(d)]
+        L.orc_transmitted_debug.restype = i32
+        L.orc_transmitted_add.argtypes = [P(OrcParams), u64, u64, u64, u32, P(d), P(d), P(u64)]
+        L.orc_transmitted_add.restype = i32
         _LIB = L
     return _LIB
 
@@ -389,9 +393,10 @@ def msa_sq(q: float, radius: float, eta: float, uc: float, ks: float) -> float:
 
 
 def trace(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0, nthreads: int = 1,
-          with_w2: bool = False, with_count: bool = False):
+          with_w2: bool = False, with_count: bool = False, transmitted: bool = False):
     """Detector (ny, nx) FP64 of neutrons first..first+n-1; optionally the
-    sum of w^2 and the hit counts."""
+    sum of w^2 and the hit counts; with transmitted, the unscattered beam
+    is added (each neutron's straight flight, weight exp(-mu_att chord))."""
     _prepare(p)
     o = to_params(p)
     det = np.zeros((p["ny"], p["nx"]))
@@ -402,9 +407,23 @@ def trace(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0, nthreads:
                          _ptr(cnt, C.c_uint64) if cnt is not None else None)
     if rc != 0:
         raise ValueError(f"oracle trace failed ({rc})")
+    if transmitted:
+        lib().orc_transmitted_add(C.byref(o), first, n, seed, exp_id, _ptr(det, C.c_double),
+                                  _ptr(w2, C.c_double) if w2 is not None else None,
+                                  _ptr(cnt, C.c_uint64) if cnt is not None else None)
     if with_w2 or with_count:
         return det, w2, cnt
     return det
+
+
+def transmitted_debug(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0):
+    """Per-neutron transmitted events (pixel, w): pixel -1 and w 0 off the
+    detector."""
+    o = to_params(p)
+    pix = np.zeros(n, dtype=np.int32)
+    w = np.zeros(n)
+    lib().orc_transmitted_debug(C.byref(o), first, n, seed, exp_id, _ptr(pix, C.c_int32), _ptr(w, C.c_double))
+    return pix, w
 
 
 def trace_debug(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0):

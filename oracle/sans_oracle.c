@@ -2157,6 +2157,77 @@ int orc_trace(const orc_params* p, uint64_t first, uint64_t n, uint64_t seed, ui
 }
 
 /* ------------------------------------------------------------------------ */
+/* The transmitted (unscattered) beam: the neutron that does not scatter
+ * keeps its straight flight from the source point through the slit point
+ * to the detector plane; the slab removes it with probability 1 -
+ * exp(-mu_att chord), so its weight is exp(-mu_att chord), the chord being
+ * its path inside the slab (zero when it misses the slab: weight 1).  Its
+ * random numbers are the first block of the neutron's stream, the same
+ * source and slit points as its scattered flight. */
+static int transmitted_one(const orc_params* p, uint64_t i, uint64_t seed, uint32_t e, double* w)
+{
+    uint32_t r0[4];
+    neutron_block(seed, i, 0, e, r0);
+    double src[3] = {(orc_uniform(r0[0]) - 0.5) * p->src_w, (orc_uniform(r0[1]) - 0.5) * p->src_h, p->src_z};
+    double slt[3] = {(orc_uniform(r0[2]) - 0.5) * p->slit_w, (orc_uniform(r0[3]) - 0.5) * p->slit_h, p->slit_z};
+    double d[3] = {slt[0] - src[0], slt[1] - src[1], slt[2] - src[2]};
+    double dl = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double ki[3] = {d[0] / dl, d[1] / dl, d[2] / dl};
+    double half[3] = {0.5 * p->sample_w, 0.5 * p->sample_h, 0.5 * p->sample_d};
+    double s_in = 0.0, s_out = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (ki[a] != 0.0) {
+            double t1 = (-half[a] - src[a]) / ki[a];
+            double t2 = (half[a] - src[a]) / ki[a];
+            double tl = t1 < t2 ? t1 : t2, th = t1 < t2 ? t2 : t1;
+            if (tl > s_in) s_in = tl;
+            if (th < s_out) s_out = th;
+        } else if (fabs(src[a]) > half[a]) {
+            s_out = -1.0;
+        }
+    }
+    double chord = s_out > s_in ? s_out - s_in : 0.0;
+    *w = exp(-p->mu_att * chord);
+    if (!(ki[2] > 0.0)) return -1;
+    double sd = (p->det_z - src[2]) / ki[2];
+    double xd = src[0] + sd * ki[0], yd = src[1] + sd * ki[1];
+    double fx = floor((xd + 0.5 * p->det_w) / (p->det_w / p->nx));
+    double fy = floor((yd + 0.5 * p->det_h) / (p->det_h / p->ny));
+    if (fx < 0.0 || fx >= p->nx || fy < 0.0 || fy >= p->ny) return -1;
+    return (int)fy * p->nx + (int)fx;
+}
+
+/* Per-neutron transmitted events: pixel (-1 off the detector) and weight
+ * (0 off the detector). */
+int orc_transmitted_debug(const orc_params* p, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
+                          int32_t* pixel, double* w)
+{
+    for (uint64_t j = 0; j < n; ++j) {
+        double wj;
+        int32_t px = transmitted_one(p, first + j, seed, exp_id, &wj);
+        pixel[j] = px;
+        w[j] = px >= 0 ? wj : 0.0;
+    }
+    return 0;
+}
+
+/* Adds the transmitted beam of neutrons first .. first+n-1 to det (and to
+ * det_w2 / det_count when given). */
+int orc_transmitted_add(const orc_params* p, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
+                        double* det, double* det_w2, uint64_t* det_count)
+{
+    for (uint64_t j = 0; j < n; ++j) {
+        double wj;
+        int32_t px = transmitted_one(p, first + j, seed, exp_id, &wj);
+        if (px < 0) continue;
+        det[px] += wj;
+        if (det_w2) det_w2[px] += wj * wj;
+        if (det_count) det_count[px] += 1;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The surrogate network, plainly: 8 -> 256 -> 256 -> 256 -> 256 -> 1 with
  * SiLU hidden units, parameters flat in the order W0[8][256] b0 W1[256][256]
  * b1 W2 b2 W3 b3 W4[256] b4 (W stored [in][out]).  FP64 arithmetic; with
