@@ -364,6 +364,7 @@ typedef enum {
 
 /* Flags. */
 #define SANS_ACCUMULATE 1u /* add to the detector instead of overwriting it     */
+#define SANS_TRANSMITTED 2u /* sans_trace_ex: also tally the unscattered beam  */
 
 /* All parameters of one virtual experiment.  Plain data; set abi_version to
  * SANS_ABI_VERSION.  Geometry in metres, wavelength and sizes in Angstrom,
@@ -474,9 +475,18 @@ int sans_trace(sans_model_t m, uint64_t n_neutrons, uint64_t seed, const sans_pa
                double* detector_out, void* stream);
 
 /* As sans_trace for neutrons first .. first+n-1 of experiment exp_id.  flags:
- * SANS_ACCUMULATE adds to det (chunked or sharded runs).  det_w2 (sum of w^2)
- * and det_count (hits, uint64) are optional device outputs (NULL = none) and
- * follow the same overwrite/accumulate rule. */
+ * SANS_ACCUMULATE adds to det (chunked or sharded runs).  SANS_TRANSMITTED
+ * also tallies the transmitted (unscattered) beam: each neutron's straight
+ * flight from its source point through its slit point (the same random
+ * numbers as its scattered flight) meets the detector plane with weight
+ * exp(-mu_att chord), the chord being its path inside the slab (1 when it
+ * misses the slab): the direct beam that the instrument's sample removes
+ * neutrons from (paper: Methods, the KWS-1 instrument and its sample
+ * component), tallied by global atomics whatever the tally mode, one per
+ * distinct pixel of each 64-neutron wave.  det_w2 (sum of w^2) and
+ * det_count (hits, uint64) are optional device outputs (NULL = none) and
+ * follow the same overwrite/accumulate rule; with SANS_TRANSMITTED they
+ * include the transmitted events. */
 int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
                   uint32_t flags, double* det, double* det_w2, uint64_t* det_count,
                   void* stream);
@@ -506,6 +516,13 @@ int sans_trace_noalloc(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed
  * sample is missed).  Any output may be NULL. */
 int sans_debug_trace(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed,
                      uint32_t exp_id, int32_t* pixel, float* w, float* q, void* stream);
+
+/* Per-neutron transmitted events of neutrons first .. first+n-1 (n at most
+ * 2^31), computed by the same device code as the SANS_TRANSMITTED tally:
+ * pixel (device int32, -1 off the detector) and w (device double, 0 off the
+ * detector). */
+int sans_debug_transmitted(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
+                           int32_t* pixel, double* w, void* stream);
 
 /* Raw Philox4x32-10 words (Salmon et al., SC'11) of the neutron streams:
  * out (device uint32 [n][n_blocks][4]) receives block b of neutron first+j,

@@ -416,6 +416,14 @@ def trace(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0, nthreads:
     return det
 
 
+def transmitted(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0) -> np.ndarray:
+    """The transmitted beam alone: detector (ny, nx) FP64."""
+    o = to_params(p)
+    det = np.zeros((p["ny"], p["nx"]))
+    lib().orc_transmitted_add(C.byref(o), first, n, seed, exp_id, _ptr(det, C.c_double), None, None)
+    return det
+
+
 def transmitted_debug(p: dict, n: int, seed: int, first: int = 0, exp_id: int = 0):
     """Per-neutron transmitted events (pixel, w): pixel -1 and w 0 off the
     detector."""

@@ -1856,6 +1856,52 @@ __device__ __forceinline__ void geom_f64(const TraceArgs& a, const U4& r0, const
     }
 }
 
+// ---------------------------------------------------------------- transmitted beam
+// The unscattered neutron: its straight flight from the source point through
+// the slit point (the first Philox block, as in its scattered flight), the
+// chord through the slab along it and the pixel where it meets the detector
+// plane; weight exp(-mu_att chord), 1 when it misses the slab.
+struct Straight {
+    int32_t pixel;   // -1: off the detector
+    double w;
+};
+
+__device__ __forceinline__ Straight straight_flight(const TraceArgs& a, uint64_t i)
+{
+    const U4 r0 = philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), 0u, a.exp_id, a.seed_lo, a.seed_hi);
+    const double sx = centred_u(r0.x) * a.src_w, sy = centred_u(r0.y) * a.src_h;
+    const double tx = centred_u(r0.z) * a.slit_w, ty = centred_u(r0.w) * a.slit_h;
+    const double dx = tx - sx, dy = ty - sy, dz = a.slit_z - a.src_z;
+    const double idl = rcp_d(sqrt_d(dx * dx + dy * dy + dz * dz));
+    const double dv[3] = {dx * idl, dy * idl, dz * idl};
+    const double o[3] = {sx, sy, a.src_z};
+    const double h[3] = {a.half_x, a.half_y, a.half_z};
+    double s_in = 0.0, s_out = 1e300;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (dv[c] != 0.0) {
+            const double inv = rcp_d(dv[c]);
+            const double t1 = (-h[c] - o[c]) * inv, t2 = (h[c] - o[c]) * inv;
+            s_in = fmax(s_in, fmin(t1, t2));
+            s_out = fmin(s_out, fmax(t1, t2));
+        } else if (fabs(o[c]) > h[c]) {
+            s_out = -1.0;
+        }
+    }
+    const double chord = s_out > s_in ? s_out - s_in : 0.0;
+    Straight st{-1, 0.0};
+    if (!(dv[2] > 0.0)) return st;
+    const double sd = div_d(a.det_z - a.src_z, dv[2]);
+    const double xd = __builtin_fma(sd, dv[0], sx), yd = __builtin_fma(sd, dv[1], sy);
+    const double fxp = floor((xd + a.det_hw) * a.inv_px);
+    const double fyp = floor((yd + a.det_hh) * a.inv_py);
+    if (fxp >= 0.0 && fxp < (double)a.nx && fyp >= 0.0 && fyp < (double)a.ny) {
+        st.pixel = (int32_t)fyp * a.nx + (int32_t)fxp;
+        st.w = exp(-a.mu_att * chord);
+    }
+    return st;
+}
+
 // The same flight in FP32 for isotropic models, measured from the slab rather
 // than the source (the entry point through the slopes dx/dz, dy/dz; the chord
 // as depth x |k|/k_z), which leaves no cancellation.  |Q| = k sqrt(2t) needs

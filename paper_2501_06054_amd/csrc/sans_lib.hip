@@ -158,6 +158,54 @@ __global__ void k_fill_u64(unsigned long long* p, size_t n)
     if (i < n) p[i] = 0ull;
 }
 
+// The transmitted beam of neutrons a.first .. a.first + a.n - 1, added to
+// det (and det_w2 / det_count when given).  One lane per neutron, the grid
+// striding in whole waves; the direct beam falls on a few pixels, so each
+// wave first merges its lanes' events pixel by pixel and issues one atomic
+// per distinct pixel.
+__global__ __launch_bounds__(256) void k_transmit(const TraceArgs a, double* det, double* det_w2,
+                                                  unsigned long long* det_count)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t base = wave * 64; base < a.n; base += nwaves * 64) {
+        const uint64_t j = base + (uint64_t)lane;
+        Straight st{-1, 0.0};
+        if (j < a.n) st = straight_flight(a, a.first + j);
+        int32_t pix = st.pixel;
+        unsigned long long pending = __ballot(pix >= 0);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            const int32_t lp = __shfl(pix, leader);
+            const bool mine = pix == lp;
+            const unsigned long long same = __ballot(mine);
+            double sw = mine ? st.w : 0.0, sw2 = sw * sw;
+            for (int off = 32; off > 0; off >>= 1) {
+                sw += __shfl_xor(sw, off);
+                sw2 += __shfl_xor(sw2, off);
+            }
+            if (lane == leader) {
+                atomicAdd(det + lp, sw);
+                if (det_w2) atomicAdd(det_w2 + lp, sw2);
+                if (det_count) atomicAdd(det_count + lp, (unsigned long long)__popcll(same));
+            }
+            if (mine) pix = -1;
+            pending &= ~same;
+        }
+    }
+}
+
+// Per-neutron transmitted events: pixel (-1 off the detector) and weight.
+__global__ __launch_bounds__(256) void k_debug_transmit(const TraceArgs a, int32_t* pixel, double* w)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
+    const Straight st = straight_flight(a, a.first + j);
+    pixel[j] = st.pixel;
+    w[j] = st.pixel >= 0 ? st.w : 0.0;
+}
+
 // det[i] (+)= sum over the XCD replicas, which are cleared for the next run.
 __global__ void k_sum_replicas(double* det, double* rep, int npix, int accumulate)
 {
@@ -1778,13 +1826,12 @@ int sans_model_constants(sans_model_t m, double* out3)
     return SANS_OK;
 }
 
-int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
-                  uint32_t flags, double* det, double* det_w2, uint64_t* det_count, void* stream)
+namespace {
+
+// The scattered neutrons' tally of sans_trace_ex (arguments checked there).
+int trace_scattered(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
+                    uint32_t flags, double* det, double* det_w2, uint64_t* det_count, void* stream)
 {
-    (void)hipGetLastError();  // a stale error of an earlier call is not ours
-    if (!m || !det) return fail(SANS_E_INVALID_ARG, "model or detector is NULL");
-    if (flags & ~SANS_ACCUMULATE) return fail(SANS_E_INVALID_ARG, "unknown flags");
-    if (n > 0 && first + n < first) return fail(SANS_E_INVALID_ARG, "neutron range overflows");
     hipStream_t s = (hipStream_t)stream;
     const size_t npix = (size_t)m->p.nx * m->p.ny;
     const bool acc = flags & SANS_ACCUMULATE;
@@ -1907,6 +1954,51 @@ int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uin
                            (int)npix, 1);
         HIP_TRY(hipGetLastError());
     }
+    return SANS_OK;
+}
+
+}  // namespace
+
+int sans_trace_ex(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
+                  uint32_t flags, double* det, double* det_w2, uint64_t* det_count, void* stream)
+{
+    (void)hipGetLastError();  // a stale error of an earlier call is not ours
+    if (!m || !det) return fail(SANS_E_INVALID_ARG, "model or detector is NULL");
+    if (flags & ~(SANS_ACCUMULATE | SANS_TRANSMITTED)) return fail(SANS_E_INVALID_ARG, "unknown flags");
+    if (n > 0 && first + n < first) return fail(SANS_E_INVALID_ARG, "neutron range overflows");
+    int rc = trace_scattered(m, first, n, seed, exp_id, flags, det, det_w2, det_count, stream);
+    if (rc || !(flags & SANS_TRANSMITTED) || n == 0) return rc;
+    TraceArgs a = m->args;
+    a.first = first;
+    a.n = n;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    a.exp_id = exp_id;
+    const unsigned grid = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>((n + 255) / 256, (uint64_t)m->num_cu * 8));
+    hipLaunchKernelGGL(k_transmit, dim3(grid), dim3(256), 0, (hipStream_t)stream, a, det, det_w2,
+                       (unsigned long long*)det_count);
+    HIP_TRY(hipGetLastError());
+    return SANS_OK;
+}
+
+int sans_debug_transmitted(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, uint32_t exp_id,
+                           int32_t* pixel, double* w, void* stream)
+{
+    (void)hipGetLastError();
+    if (!m || !pixel || !w) return fail(SANS_E_INVALID_ARG, "NULL argument");
+    if (n > ((uint64_t)1 << 31)) return fail(SANS_E_INVALID_ARG, "n must be at most 2^31");
+    if (n > 0 && first + n < first) return fail(SANS_E_INVALID_ARG, "neutron range overflows");
+    if (n == 0) return SANS_OK;
+    TraceArgs a = m->args;
+    a.first = first;
+    a.n = n;
+    a.seed_lo = (uint32_t)seed;
+    a.seed_hi = (uint32_t)(seed >> 32);
+    a.exp_id = exp_id;
+    hipLaunchKernelGGL(k_debug_transmit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, a,
+                       pixel, w);
+    HIP_TRY(hipGetLastError());
     return SANS_OK;
 }
 

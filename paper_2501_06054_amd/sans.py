@@ -23,6 +23,7 @@ SANS_E_NOMEM = -3
 SANS_E_HIP = -4
 SANS_E_DOMAIN = -5
 SANS_ACCUMULATE = 1
+SANS_TRANSMITTED = 2
 
 KIND = {"sphere": 0, "core_shell": 1, "cylinder": 2, "ellipsoid": 3, "parallelepiped": 4,
         "barbell": 5, "capped_cylinder": 6, "hollow_prism": 7,
@@ -88,6 +89,7 @@ def _load():
     L.sans_trace_ex.argtypes = [vp, u64, u64, u64, u32, u32, vp, vp, vp, vp]
     L.sans_trace_noalloc.argtypes = [vp, u64, u64, u64, u32, u32, vp, vp]
     L.sans_debug_trace.argtypes = [vp, u64, u64, u64, u32, vp, vp, vp, vp]
+    L.sans_debug_transmitted.argtypes = [vp, u64, u64, u64, u32, vp, vp, vp]
     L.sans_debug_philox.argtypes = [u64, u64, u64, u32, u32, vp, vp]
     L.sans_debug_table.argtypes = [vp, i32, P(C.c_double), i32]
     L.sans_debug_weight_scale.argtypes = [P(sans_params), P(C.c_double), P(C.c_double)]
@@ -119,7 +121,8 @@ def _load():
     L.sans_status_string.restype = C.c_char_p
     L.sans_last_error.restype = C.c_char_p
     for f in ("sans_model_create", "sans_model_destroy", "sans_trace", "sans_trace_ex", "sans_trace_noalloc",
-              "sans_debug_trace", "sans_debug_philox", "sans_debug_table", "sans_debug_weight_scale", "sans_pq_avg",
+              "sans_debug_trace", "sans_debug_transmitted", "sans_debug_philox", "sans_debug_table",
+              "sans_debug_weight_scale", "sans_pq_avg",
               "sans_model_constants", "sans_trace_batch", "sans_batch_release"):
         getattr(L, f).restype = C.c_int
     return L
@@ -227,6 +230,11 @@ def sans_debug_trace(h, first: int, n: int, seed: int, exp_id: int, pixel=None, 
     _check(lib.sans_debug_trace(h, first, n, seed, exp_id, _dev(pixel, torch.int32, "pixel"),
                                 _dev(w, torch.float32, "w"), _dev(q, torch.float32, "q"),
                                 _stream(stream)), "sans_debug_trace")
+
+
+def sans_debug_transmitted(h, first: int, n: int, seed: int, exp_id: int, pixel, w, stream=None) -> None:
+    _check(lib.sans_debug_transmitted(h, first, n, seed, exp_id, _dev(pixel, torch.int32, "pixel"),
+                                      _dev(w, torch.float64, "w"), _stream(stream)), "sans_debug_transmitted")
 
 
 def sans_debug_philox(seed: int, first: int, n: int, n_blocks: int, exp_id: int, out,
@@ -382,12 +390,19 @@ class Model:
                            device="cuda")
 
     def trace(self, n: int, seed: int, det=None, first: int = 0, exp_id: int = 0,
-              accumulate: bool = False, det_w2=None, det_count=None, stream=None):
+              accumulate: bool = False, det_w2=None, det_count=None, stream=None,
+              transmitted: bool = False):
         if det is None:
             det = self.detector()
-        sans_trace_ex(self.handle, first, n, seed, exp_id, SANS_ACCUMULATE if accumulate else 0,
-                      det, det_w2, det_count, stream)
+        flags = (SANS_ACCUMULATE if accumulate else 0) | (SANS_TRANSMITTED if transmitted else 0)
+        sans_trace_ex(self.handle, first, n, seed, exp_id, flags, det, det_w2, det_count, stream)
         return det
+
+    def debug_transmitted(self, n: int, seed: int, first: int = 0, exp_id: int = 0):
+        pix = torch.empty(n, dtype=torch.int32, device="cuda")
+        w = torch.empty(n, dtype=torch.float64, device="cuda")
+        sans_debug_transmitted(self.handle, first, n, seed, exp_id, pix, w)
+        return pix, w
 
     def debug_trace(self, n: int, seed: int, first: int = 0, exp_id: int = 0):
         pix = torch.empty(n, dtype=torch.int32, device="cuda")

@@ -439,6 +439,87 @@ def test_pq_avg_matches_oracle(S):
         m.close()
 
 
+# ------------------------------------------------------------------ transmitted beam
+
+TRANSMIT_CASES = {
+    "attenuated_coreshell": dict(W.workload("coreshell_py")["params"], mu_att=150.0),
+    "divergent_thick": W.params(sample_w=0.05, sample_h=0.05, sample_d=0.003, mu_att=400.0, src_w=0.03,
+                                src_h=0.02, slit_w=0.012, slit_h=0.008, src_z=-1.0, nx=257, ny=257,
+                                det_w=1.0, det_h=1.0),
+    "around_opaque_slab": W.params(src_w=0.02, src_h=0.004, slit_w=0.02, slit_h=0.004, src_z=-4.0,
+                                   slit_z=-2.0, sample_w=0.03, sample_h=0.1, sample_d=0.001, mu_att=1e7,
+                                   det_w=0.3, det_h=0.3),
+    "no_attenuation_cylinder": W.params(kind="cylinder", size=(20.0, 80.0, 0), orient_kind="isotropic"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(TRANSMIT_CASES))
+def test_transmitted_per_neutron(S, name):
+    p = TRANSMIT_CASES[name]
+    n, seed = 200_003, 13
+    for first in (0, 2**35 + 7):
+        log(f"transmitted per-neutron {name} first={first} n={n}")
+        m = S.Model(p)
+        pix, w = m.debug_transmitted(n, seed, first=first, exp_id=3)
+        torch.cuda.synchronize()
+        opix, ow = oracle.transmitted_debug(p, n, seed, first=first, exp_id=3)
+        assert np.array_equal(pix.cpu().numpy(), opix)
+        # w <= 1; the chord's rounding (a few 1e-16 m, from crossing points
+        # metres away) enters as exp(-mu delta) and is visible in relative
+        # terms only where w is negligible (opaque slabs, corner cuts)
+        np.testing.assert_allclose(w.cpu().numpy(), ow, rtol=1e-12, atol=1e-15)
+        m.close()
+
+
+@pytest.mark.parametrize("name", sorted(TRANSMIT_CASES))
+@pytest.mark.parametrize("tally", ["auto", "global", "lds", "xcd", "binned"])
+def test_transmitted_detector(S, name, tally):
+    """The detector with the transmitted beam minus the one without it is the
+    oracle's transmitted beam (FP64 weights; only the order of the atomic
+    sums differs), and the hit counts add exactly."""
+    p = TRANSMIT_CASES[name]
+    n, seed = 300_007, 17
+    log(f"transmitted detector {name} tally={tally} n={n}")
+    m = S.Model(p, tally=tally)
+    det = m.trace(n, seed)
+    both = m.trace(n, seed, transmitted=True)
+    torch.cuda.synchronize()
+    ref = oracle.transmitted(p, n, seed)
+    got = both.cpu().numpy() - det.cpu().numpy()
+    scale = float(np.abs(both.cpu().numpy()).max())
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12 * scale)
+    m.close()
+
+
+def test_transmitted_with_w2_counts_and_accumulate(S):
+    p = TRANSMIT_CASES["attenuated_coreshell"]
+    n, seed = 200_003, 19
+    log("transmitted w2/count/accumulate")
+    m = S.Model(p)
+    det = m.detector()
+    w2 = torch.zeros_like(det)
+    cnt = torch.zeros(det.shape, dtype=torch.int64, device="cuda")
+    half = n // 2
+    m.trace(half, seed, det=det, det_w2=w2, det_count=cnt, transmitted=True)
+    m.trace(n - half, seed, det=det, det_w2=w2, det_count=cnt, first=half, accumulate=True, transmitted=True)
+    torch.cuda.synchronize()
+    rdet, rw2, rcnt = oracle.trace(p, n, seed, nthreads=NTHREADS, with_w2=True, with_count=True, transmitted=True)
+    assert np.array_equal(cnt.cpu().numpy().astype(np.uint64), rcnt)
+    beam = rcnt > 1000
+    np.testing.assert_allclose(det.cpu().numpy()[beam], rdet[beam], rtol=1e-9)
+    np.testing.assert_allclose(w2.cpu().numpy()[beam], rw2[beam], rtol=1e-9)
+    assert abs(det.cpu().numpy().sum() - rdet.sum()) <= 1e-9 * rdet.sum()
+    m.close()
+
+
+def test_transmitted_rejects_unknown_flags(S):
+    m = S.Model(W.workload("tiny_sphere")["params"])
+    det = m.detector()
+    with pytest.raises(RuntimeError):
+        S.sans_trace_ex(m.handle, 0, 10, 1, 0, 4, det)
+    m.close()
+
+
 # ------------------------------------------------------------------ edge cases
 
 def test_zero_neutrons_clears_detector(S):
