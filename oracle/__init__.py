@@ -60,7 +60,7 @@ class OrcParams(C.Structure):
         ("table_size", C.c_int32), ("quad_n", C.c_int32),
         ("poly_kind", C.c_int32), ("sq_kind", C.c_int32),
         ("extra", C.c_double * 4), ("sq_extra", C.c_double * 2), ("mu_att", C.c_double),
-        ("poly_sep", C.c_double * 3),
+        ("poly_sep", C.c_double * 3), ("guide", C.c_double * 9),
     ]
 
 
@@ -188,8 +188,23 @@ def lib():
         L.orc_transmitted_debug.restype = i32
         L.orc_transmitted_add.argtypes = [P(OrcParams), u64, u64, u64, u32, P(d), P(d), P(u64)]
         L.orc_transmitted_add.restype = i32
+        L.orc_guide_weight.argtypes = [P(OrcParams), P(d), P(d), d]
+        L.orc_guide_weight.restype = d
         _LIB = L
     return _LIB
+
+
+GUIDE_FIELDS = ("guide_len", "guide_w", "guide_h", "guide_gap", "guide_m", "guide_r0", "guide_qc",
+                "guide_alpha", "guide_wc")
+
+
+def guide_weight(p: dict, src, ki, lam: float) -> float:
+    """The guide's weight of a neutron reaching the source aperture at src
+    (m) along the unit vector ki with wavelength lam (A)."""
+    o = to_params(p)
+    a = np.ascontiguousarray(src, dtype=np.float64)
+    b = np.ascontiguousarray(ki, dtype=np.float64)
+    return lib().orc_guide_weight(C.byref(o), _ptr(a, C.c_double), _ptr(b, C.c_double), float(lam))
 
 
 def _ptr(a, ctype):
@@ -224,6 +239,8 @@ def to_params(p: dict) -> OrcParams:
         o.sq_extra[k] = float(v)
     for k, v in enumerate(p.get("poly_sep", (0.0, 0.0, 0.0))):
         o.poly_sep[k] = float(v)
+    for k, f in enumerate(GUIDE_FIELDS):
+        o.guide[k] = float(p.get(f, 0.0))
     return o
 
 

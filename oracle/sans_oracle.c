@@ -126,6 +126,10 @@ typedef struct {
                               "Polydispersity ...", Eq. (8)): size[k] times
                               its own draw y_k ~ N(1, poly_sep[k]^2) kept
                               where positive; 0 -> size[k] fixed            */
+    double guide[9];       /* straight guide upstream of the source aperture:
+                              length (m; 0 -> none), width, height, gap from
+                              its exit to the aperture (m), supermirror m,
+                              R0, Qc (1/A), alpha (A), W (1/A)              */
 } orc_params;
 
 /* Surrogate mode (mode 2): a network replaces the exact average; set with
@@ -1890,6 +1894,66 @@ static void ctx_free(orc_ctx* cx)
     for (int k = 0; k < 3; ++k) free(cx->tab_sep[k]);
 }
 
+/* The neutron guide (an upstream instrument component of the paper's
+ * KWS-1 simulation, Methods): a straight rectangular channel of length L,
+ * width w and height h whose exit lies a gap g upstream of the source
+ * aperture, its walls supermirrors of reflectivity (the usual form for
+ * them)
+ *   R(Q) = R0                                                  Q <= Qc,
+ *   R(Q) = R0/2 (1 - tanh((Q - m Qc)/W)) (1 - alpha (Q - Qc))  Q > Qc,
+ * (0 where that is negative), Q = 4 pi sin(theta)/lambda for the grazing
+ * angle theta.  The moderator fills the guide's entrance.  A neutron that
+ * reaches the source aperture at src flying along ki is followed back: to
+ * the exit plane (it must pass inside the exit, else nothing feeds it:
+ * weight 0), then inside the guide wall by wall, reflecting off each wall
+ * it meets, until it reaches the entrance plane; its weight is the product
+ * of the reflectivities met. */
+static double guide_reflectivity(const orc_params* p, double q)
+{
+    const double r0 = p->guide[5], qc = p->guide[6], alpha = p->guide[7], wc = p->guide[8], m = p->guide[4];
+    if (q <= qc) return r0;
+    double r = 0.5 * r0 * (1.0 - tanh((q - m * qc) / wc)) * (1.0 - alpha * (q - qc));
+    return r > 0.0 ? r : 0.0;
+}
+
+static double guide_weight(const orc_params* p, const double src[3], const double ki[3], double lambda)
+{
+    if (!(p->guide[0] > 0.0)) return 1.0;
+    const double len = p->guide[0], hw = 0.5 * p->guide[1], hh = 0.5 * p->guide[2], gap = p->guide[3];
+    /* back along -ki from the aperture to the exit plane z_src - gap */
+    double t = gap / ki[2];
+    double x = src[0] - t * ki[0], y = src[1] - t * ki[1], z = src[2] - gap;
+    if (fabs(x) > hw || fabs(y) > hh) return 0.0;
+    double dx = -ki[0], dy = -ki[1], dz = -ki[2];
+    const double z_in = src[2] - gap - len;
+    const double qx = 4.0 * ORC_PI * fabs(ki[0]) / lambda, qy = 4.0 * ORC_PI * fabs(ki[1]) / lambda;
+    const double rx = guide_reflectivity(p, qx), ry = guide_reflectivity(p, qy);
+    double w = 1.0;
+    for (int step = 0; step < 1000000; ++step) {
+        double tz = (z_in - z) / dz;
+        double tx = dx > 0.0 ? (hw - x) / dx : dx < 0.0 ? (-hw - x) / dx : INFINITY;
+        double ty = dy > 0.0 ? (hh - y) / dy : dy < 0.0 ? (-hh - y) / dy : INFINITY;
+        if (tz <= tx && tz <= ty) return w;       /* the entrance */
+        if (tx <= ty) {
+            x += tx * dx; y += tx * dy; z += tx * dz;
+            x = dx > 0.0 ? hw : -hw;
+            dx = -dx;
+            w *= rx;
+        } else {
+            x += ty * dx; y += ty * dy; z += ty * dz;
+            y = dy > 0.0 ? hh : -hh;
+            dy = -dy;
+            w *= ry;
+        }
+    }
+    return w;
+}
+
+double orc_guide_weight(const orc_params* p, const double src[3], const double ki[3], double lambda)
+{
+    return guide_weight(p, src, ki, lambda);
+}
+
 static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_t e)
 {
     const orc_params* p = cx->p;
@@ -2008,7 +2072,7 @@ static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_
         if (!in_domain) f2 = pq_avg_nodes(p, q, qv, cx->gx, cx->gw);
     }
     double sq = struct_factor(p, q);
-    double w = len * 1e10 * cx->prefactor * f2 * sq;
+    double w = len * 1e10 * cx->prefactor * f2 * sq * guide_weight(p, src, ki, lambda);
     /* attenuation: exp(-mu (path before the scattering point + path after it
        along kf to where the slab is left)) */
     if (p->mu_att > 0.0) {
@@ -2188,6 +2252,12 @@ static int transmitted_one(const orc_params* p, uint64_t i, uint64_t seed, uint3
     }
     double chord = s_out > s_in ? s_out - s_in : 0.0;
     *w = exp(-p->mu_att * chord);
+    if (p->guide[0] > 0.0) {
+        uint32_t r1[4];
+        neutron_block(seed, i, 1, e, r1);
+        double lambda = p->lambda0 * (1.0 + p->dlambda_rel * (2.0 * orc_uniform(r1[0]) - 1.0));
+        *w *= guide_weight(p, src, ki, lambda);
+    }
     if (!(ki[2] > 0.0)) return -1;
     double sd = (p->det_z - src[2]) / ki[2];
     double xd = src[0] + sd * ki[0], yd = src[1] + sd * ki[1];

@@ -63,6 +63,11 @@ INSTRUMENT = dict(
     sample_w=0.010, sample_h=0.010, sample_d=0.001,
     det_w=0.6, det_h=0.6, det_z=5.0,
     nx=128, ny=128,
+    # straight supermirror guide upstream of the source aperture (length 0:
+    # none); reflectivity R0, Qc (1/A), alpha (A), W (1/A) of common m-coated
+    # mirrors
+    guide_len=0.0, guide_w=0.03, guide_h=0.03, guide_gap=0.5, guide_m=2.0,
+    guide_r0=0.99, guide_qc=0.0219, guide_alpha=6.07, guide_wc=0.003,
 )
 
 SAMPLE_DEFAULTS = dict(
