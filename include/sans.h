@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SANS_ABI_VERSION 6u
+#define SANS_ABI_VERSION 7u
 
 /* Status codes. */
 #define SANS_OK 0
@@ -447,6 +447,29 @@ typedef struct {
                                 (k <= 2), whose volumes are products of
                                 powers of the sizes (<V> = V prod <y_k^e_k>);
                                 the batched launch refuses it              */
+    double guide[9];         /* a straight neutron guide upstream of the
+                                source aperture (the paper's KWS-1
+                                instrument brings the beam to its apertures
+                                through guides; Methods): length guide[0] (m;
+                                0 = no guide), width guide[1] and height
+                                guide[2] (m, centred on the beam axis), gap
+                                guide[3] (m) from its exit to the source
+                                aperture, supermirror m = guide[4] and the
+                                reflectivity R0 = guide[5], Qc = guide[6]
+                                (1/A), alpha = guide[7] (A), W = guide[8]
+                                (1/A): R(Q) = R0 up to Qc, then R0/2 (1 -
+                                tanh((Q - m Qc)/W)) (1 - alpha (Q - Qc)),
+                                0 where negative.  The moderator fills the
+                                guide's entrance; each traced neutron is
+                                followed back from its source point along its
+                                flight: its weight is 0 if it misses the
+                                guide's exit, else R(Q_x)^n_x R(Q_y)^n_y for
+                                its n_x and n_y reflections (Q = 4 pi
+                                sin(grazing angle)/lambda).  Also weights the
+                                transmitted beam.  Runs with a guide tally
+                                with atomics like attenuated ones; the
+                                batched launch and the surrogate mode refuse
+                                a guide                                     */
 } sans_params;
 
 typedef struct sans_model_s* sans_model_t;

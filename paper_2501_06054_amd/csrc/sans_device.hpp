@@ -79,6 +79,10 @@ struct TraceArgs {
     double clear_x, clear_y;      // the half-widths less 1e-9 of themselves
     double omc;                   // 1 - cos(alpha)
     double mu_att;                // attenuation coefficient (1/m)
+    // the guide upstream of the source aperture (guide_on: length > 0):
+    // half-width, half-height, length, gap to the aperture, reflectivity
+    int32_t guide_on;
+    double guide_hw, guide_hh, guide_len, guide_gap, guide_m, guide_r0, guide_qc, guide_alpha, guide_wc;
     int32_t att_on;               // mu_att > 0 (an integer: the branch stays scalar)
     double det_z, det_hw, det_hh;
     double inv_px, inv_py;        // nx / det_w, ny / det_h
@@ -1856,6 +1860,52 @@ __device__ __forceinline__ void geom_f64(const TraceArgs& a, const U4& r0, const
     }
 }
 
+// ---------------------------------------------------------------- guide
+// Supermirror reflectivity: R0 up to Qc, then R0/2 (1 - tanh((Q - m Qc)/W))
+// (1 - alpha (Q - Qc)), 0 where negative.
+__device__ __forceinline__ double guide_reflectivity(const TraceArgs& a, double q)
+{
+    if (q <= a.guide_qc) return a.guide_r0;
+    const double r = 0.5 * a.guide_r0 * (1.0 - tanh((q - a.guide_m * a.guide_qc) / a.guide_wc))
+                     * (1.0 - a.guide_alpha * (q - a.guide_qc));
+    return fmax(r, 0.0);
+}
+
+// The guide's weight of a neutron that reaches the source aperture at
+// (sx, sy) flying along the unit vector k with wavelength lambda: back to the
+// exit plane (outside the exit: 0), then through the guide as the straight
+// line unfolded across the walls -- a wall plane crossed is a reflection at
+// the same grazing angle, |floor((x_entrance + w/2)/w)| of them across x
+// (likewise y) -- R(Q_x)^n_x R(Q_y)^n_y, Q = 4 pi |k_x| / lambda.
+__device__ __forceinline__ double guide_weight(const TraceArgs& a, double sx, double sy, const double k[3],
+                                               double lambda)
+{
+    const double ikz = rcp_d(k[2]);
+    const double ex = sx - a.guide_gap * k[0] * ikz, ey = sy - a.guide_gap * k[1] * ikz;
+    if (fabs(ex) > a.guide_hw || fabs(ey) > a.guide_hh) return 0.0;
+    const double xu = ex - a.guide_len * k[0] * ikz, yu = ey - a.guide_len * k[1] * ikz;
+    const double nx = fabs(floor((xu + a.guide_hw) / (2.0 * a.guide_hw)));
+    const double ny = fabs(floor((yu + a.guide_hh) / (2.0 * a.guide_hh)));
+    const double fq = 4.0 * kPi / lambda;
+    double w = 1.0;
+    if (nx > 0.0) w *= pow(guide_reflectivity(a, fq * fabs(k[0])), nx);
+    if (ny > 0.0) w *= pow(guide_reflectivity(a, fq * fabs(k[1])), ny);
+    return w;
+}
+
+// The guide's weight of neutron (r0, r1): its source and slit points and
+// wavelength as in its flight (FP64).
+__device__ __forceinline__ double guide_weight_of(const TraceArgs& a, const U4& r0, const U4& r1)
+{
+    const double sx = centred_u(r0.x) * a.src_w, sy = centred_u(r0.y) * a.src_h;
+    const double tx = centred_u(r0.z) * a.slit_w, ty = centred_u(r0.w) * a.slit_h;
+    const double dx = tx - sx, dy = ty - sy, dz = a.slit_z - a.src_z;
+    const double idl = rcp_d(sqrt_d(dx * dx + dy * dy + dz * dz));
+    const double k[3] = {dx * idl, dy * idl, dz * idl};
+    const double lambda = __builtin_fma(a.lambda_span, 2.0 * u64(r1.x) - 1.0, a.lambda0);
+    return guide_weight(a, sx, sy, k, lambda);
+}
+
 // ---------------------------------------------------------------- transmitted beam
 // The unscattered neutron: its straight flight from the source point through
 // the slit point (the first Philox block, as in its scattered flight), the
@@ -1898,6 +1948,11 @@ __device__ __forceinline__ Straight straight_flight(const TraceArgs& a, uint64_t
     if (fxp >= 0.0 && fxp < (double)a.nx && fyp >= 0.0 && fyp < (double)a.ny) {
         st.pixel = (int32_t)fyp * a.nx + (int32_t)fxp;
         st.w = exp(-a.mu_att * chord);
+        if (a.guide_on) {
+            const U4 r1 = philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), 1u, a.exp_id, a.seed_lo, a.seed_hi);
+            const double lambda = __builtin_fma(a.lambda_span, 2.0 * u64(r1.x) - 1.0, a.lambda0);
+            st.w *= guide_weight(a, sx, sy, dv, lambda);
+        }
     }
     return st;
 }
@@ -2103,7 +2158,10 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
     }
     float w = geo.len * a.f_wscale * f2;
     if (a.sq_on) w *= struct_factor(a, q);
-    if constexpr (ATT) w *= att;
+    if constexpr (ATT) {
+        w *= att;
+        if (a.guide_on) w *= (float)guide_weight_of(a, r0, r1);
+    }
     if (on_det) {
         ev.pixel = geo.pixel;
         ev.w = w;

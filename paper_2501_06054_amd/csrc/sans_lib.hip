@@ -855,6 +855,16 @@ int validate(const sans_params* p)
     if (!(p->phi >= 0.0 && p->phi < 1.0)) return fail(SANS_E_INVALID_ARG, "phi must be in [0, 1)");
     if (!(p->sq_phi >= 0.0 && p->sq_phi < 0.6)) return fail(SANS_E_INVALID_ARG, "sq_phi must be in [0, 0.6)");
     if (!(p->mu_att >= 0.0 && finite(p->mu_att))) return fail(SANS_E_INVALID_ARG, "mu_att must be >= 0");
+    if (!(p->guide[0] >= 0.0 && finite(p->guide[0]))) return fail(SANS_E_INVALID_ARG, "guide length must be >= 0");
+    if (p->guide[0] > 0.0) {
+        const double* g = p->guide;
+        if (!(g[1] > 0.0 && finite(g[1]) && g[2] > 0.0 && finite(g[2]) && g[3] >= 0.0 && finite(g[3])))
+            return fail(SANS_E_INVALID_ARG, "guide: width and height must be > 0 and the gap >= 0");
+        if (!(g[4] > 0.0 && finite(g[4]) && g[5] > 0.0 && g[5] <= 1.0 && g[6] > 0.0 && finite(g[6])
+              && g[7] >= 0.0 && finite(g[7]) && g[8] > 0.0 && finite(g[8])))
+            return fail(SANS_E_INVALID_ARG, "guide: need m > 0, R0 in (0, 1], Qc > 0, alpha >= 0 and W > 0");
+        if (p->mode == SANS_MODE_SURROGATE) return fail(SANS_E_UNSUPPORTED, "surrogate mode: no guide");
+    }
     if (p->mu_att > 0.0 && p->mode == SANS_MODE_SURROGATE)
         return fail(SANS_E_UNSUPPORTED, "surrogate mode: no attenuation");
     if (p->sq_phi > 0.0 && !(p->sq_radius > 0.0)) return fail(SANS_E_INVALID_ARG, "sq_radius must be > 0");
@@ -1033,6 +1043,16 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
     a.omc = *omc;
     a.mu_att = p->mu_att;
     a.att_on = p->mu_att > 0.0;
+    a.guide_on = p->guide[0] > 0.0;
+    a.guide_len = p->guide[0];
+    a.guide_hw = 0.5 * p->guide[1];
+    a.guide_hh = 0.5 * p->guide[2];
+    a.guide_gap = p->guide[3];
+    a.guide_m = p->guide[4];
+    a.guide_r0 = p->guide[5];
+    a.guide_qc = p->guide[6];
+    a.guide_alpha = p->guide[7];
+    a.guide_wc = p->guide[8];
     a.det_z = p->det_z;
     a.det_hw = 0.5 * p->det_w;
     a.det_hh = 0.5 * p->det_h;
@@ -1526,8 +1546,10 @@ int choose_tally(const sans_model_s* m, bool extras)
 {
     int t = m->p.tally;
     // the optional sum-of-squares and count outputs use the atomic path, and
-    // so do attenuated runs (only the atomic-tally kernels carry it)
-    if (extras || m->p.mu_att > 0.0) return t == SANS_TALLY_XCD ? SANS_TALLY_XCD : SANS_TALLY_GLOBAL;
+    // so do runs with attenuation or a guide (only the atomic-tally kernels
+    // carry them)
+    if (extras || m->p.mu_att > 0.0 || m->p.guide[0] > 0.0)
+        return t == SANS_TALLY_XCD ? SANS_TALLY_XCD : SANS_TALLY_GLOBAL;
     // the exact average spends thousands of operations per tallied neutron:
     // plain atomics cost nothing there, and the workgroup histogram's LDS
     // would halve the waves per SIMD
@@ -2070,7 +2092,7 @@ int sans_debug_trace(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, 
     a.seed_hi = (uint32_t)(seed >> 32);
     a.exp_id = exp_id;
     const LdsLayout lay = layout(m, false);
-    DebugFn fn = pick_debug(m->p.kind, m->p.mode, m->p.mu_att > 0.0);
+    DebugFn fn = pick_debug(m->p.kind, m->p.mode, m->p.mu_att > 0.0 || m->p.guide[0] > 0.0);
     if (!fn) return fail(SANS_E_UNSUPPORTED, "no kernel for this model");
     hipLaunchKernelGGL(fn, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), lds_bytes(lay),
                        (hipStream_t)stream, a, lay, pixel, w, q);
@@ -2456,6 +2478,8 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
         int rc = validate(&p[e]);
         if (rc == SANS_OK && p[e].mu_att > 0.0)
             rc = fail(SANS_E_UNSUPPORTED, "batched launch: no attenuation (trace attenuated experiments one by one)");
+        if (rc == SANS_OK && p[e].guide[0] > 0.0)
+            rc = fail(SANS_E_UNSUPPORTED, "batched launch: no guide (trace such experiments one by one)");
         if (rc == SANS_OK && (p[e].poly_sep[0] > 0.0 || p[e].poly_sep[1] > 0.0 || p[e].poly_sep[2] > 0.0))
             rc = fail(SANS_E_UNSUPPORTED, "batched launch: no independent size widths");
         if (rc) return rc;

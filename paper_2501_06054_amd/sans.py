@@ -15,13 +15,15 @@ import torch  # loaded first so that libsans shares PyTorch's HIP runtime
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsans.so")
 
-SANS_ABI_VERSION = 6
+SANS_ABI_VERSION = 7
 SANS_OK = 0
 SANS_E_INVALID_ARG = -1
 SANS_E_UNSUPPORTED = -2
 SANS_E_NOMEM = -3
 SANS_E_HIP = -4
 SANS_E_DOMAIN = -5
+GUIDE_FIELDS = ("guide_len", "guide_w", "guide_h", "guide_gap", "guide_m", "guide_r0", "guide_qc",
+                "guide_alpha", "guide_wc")
 SANS_ACCUMULATE = 1
 SANS_TRANSMITTED = 2
 
@@ -72,7 +74,7 @@ class sans_params(C.Structure):
         ("nx", C.c_int32), ("ny", C.c_int32), ("quad_n", C.c_int32), ("tally", C.c_int32),
         ("poly_kind", C.c_int32), ("sq_kind", C.c_int32),
         ("extra", C.c_double * 4), ("sq_extra", C.c_double * 2), ("mu_att", C.c_double),
-        ("poly_sep", C.c_double * 3),
+        ("poly_sep", C.c_double * 3), ("guide", C.c_double * 9),
     ]
 
 
@@ -186,6 +188,8 @@ def to_params(p: dict, tally: str = "auto") -> sans_params:
         s.sq_extra[k] = float(v)
     for k, v in enumerate(p.get("poly_sep", (0.0, 0.0, 0.0))):
         s.poly_sep[k] = float(v)
+    for k, f in enumerate(GUIDE_FIELDS):
+        s.guide[k] = float(p.get(f, 0.0))
     return s
 
 

@@ -176,6 +176,10 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
     # a deep, wide well drives 1/S(0) below zero
     (dict(kind="sphere", sq_phi=0.2, sq_radius=50.0, sq_kind="square_well", sq_extra=(3.0, 2.0)),
      "SANS_E_DOMAIN"),
+    (dict(kind="sphere", guide_len=-1.0), "SANS_E_INVALID_ARG"),
+    (dict(kind="sphere", guide_len=5.0, guide_w=0.0), "SANS_E_INVALID_ARG"),
+    (dict(kind="sphere", guide_len=5.0, guide_r0=1.2), "SANS_E_INVALID_ARG"),
+    (dict(kind="sphere", guide_len=5.0, guide_wc=0.0), "SANS_E_INVALID_ARG"),
     (dict(kind="flexible_cylinder", size=(10.0, 500.0, 0.0), extra=(0.0, 0, 0, 0)), "SANS_E_INVALID_ARG"),
     (dict(kind="flexible_cylinder", size=(10.0, 500.0, 0.0), extra=(50.0, 0, 0, 0), mode="quad",
           orient_kind="isotropic"), "SANS_E_UNSUPPORTED"),

@@ -159,12 +159,15 @@ def test_batch_rejects_mismatched_detectors(S):
         S.sans_trace_batch([exps[0]["params"], p1], [10, 10], [1, 1], out)
 
 
-def test_batch_rejects_attenuation(S):
+def test_batch_rejects_attenuation_and_guides(S):
     exps = _small_batch(n_exp=2)
     p1 = dict(exps[1]["params"], mu_att=50.0)
     out = torch.empty((2, 128, 128), dtype=torch.float64, device="cuda")
     with pytest.raises(S.SansError):
         S.sans_trace_batch([exps[0]["params"], p1], [10, 10], [1, 1], out)
+    p2 = dict(exps[1]["params"], guide_len=10.0)
+    with pytest.raises(S.SansError):
+        S.sans_trace_batch([exps[0]["params"], p2], [10, 10], [1, 1], out)
 
 
 def test_batch_gaussian_sizes(S):

@@ -330,6 +330,13 @@ PER_NEUTRON = {
                                             sld=(1e-6, 3e-6, 6.3e-6), phi=0.05, poly=0.15, poly_mask=1,
                                             sq_phi=0.05, sq_radius=48.0, sq_kind="hayter_msa",
                                             sq_extra=(3.0, 0.4)), 20011),
+    # a supermirror guide upstream of the source aperture (reflections
+    # counted on the unfolded line; the oracle bounces wall by wall)
+    "guided_coreshell": (dict(W.workload("coreshell_py")["params"], guide_len=14.0, guide_w=0.012,
+                              guide_h=0.012, guide_gap=0.4, guide_m=1.5), 30011),
+    "guided_oriented_cylinder_attenuated": (dict(W.workload("oriented_cylinder")["params"], guide_len=20.0,
+                                                 guide_w=0.008, guide_h=0.02, guide_gap=1.0, guide_m=3.0,
+                                                 lambda0=10.0, dlambda_rel=0.1, mu_att=120.0), 30011),
     # pringle (complex amplitude, a polar rule per event)
     "pringle_iso": (W.params(kind="pringle", size=(60.0, 10.0, 0), extra=(0.001, 0.02, 0, 0), quad_n=16,
                              orient_kind="isotropic"), 10011),
@@ -370,7 +377,8 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "belt_bicelle_gauss", "raspberry_poly", "pearl_necklace", "binary_hard_sphere",
              "adsorbed_layer", "pringle_iso", "attenuated_coreshell", "poly_sep_cylinder",
              "poly_sep_parallelepiped", "poly_sep_ellipsoid_gauss", "flexible_cylinder_elliptical",
-             "flexcyl_flexible_flat", "charged_spheres", "hayter_strong_cylinder", "flexible_cylinder"]
+             "flexcyl_flexible_flat", "charged_spheres", "hayter_strong_cylinder", "flexible_cylinder",
+             "guided_coreshell"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
@@ -450,6 +458,10 @@ TRANSMIT_CASES = {
                                    slit_z=-2.0, sample_w=0.03, sample_h=0.1, sample_d=0.001, mu_att=1e7,
                                    det_w=0.3, det_h=0.3),
     "no_attenuation_cylinder": W.params(kind="cylinder", size=(20.0, 80.0, 0), orient_kind="isotropic"),
+    "guided_divergent": W.params(sample_w=0.05, sample_h=0.05, sample_d=0.003, mu_att=400.0, src_w=0.03,
+                                 src_h=0.02, slit_w=0.012, slit_h=0.008, src_z=-1.0, nx=257, ny=257,
+                                 det_w=1.0, det_h=1.0, guide_len=12.0, guide_w=0.02, guide_h=0.015,
+                                 guide_gap=0.3, guide_m=2.5, lambda0=5.0),
 }
 
 
