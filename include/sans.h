@@ -426,10 +426,12 @@ typedef struct {
                                 (path inside the slab before the scattering
                                 point + path after it to where the scattered
                                 neutron leaves the slab)); 0 = none.
-                                Attenuated runs tally with atomics (GLOBAL,
-                                or XCD when asked for), whatever `tally`
-                                asks; the batched launch and the surrogate
-                                mode refuse them (SANS_E_UNSUPPORTED)       */
+                                Attenuated Monte Carlo runs take any tally
+                                (their own kernel instances); attenuated
+                                exact-average runs tally with atomics
+                                (GLOBAL, or XCD when asked for); the batched
+                                launch and the surrogate mode refuse them
+                                (SANS_E_UNSUPPORTED)                        */
     double poly_sep[3];      /* independent relative widths (the paper's rule,
                                 Methods, "Polydispersity and orientational
                                 distributions", Eq. (8): each radius or
@@ -466,8 +468,8 @@ typedef struct {
                                 guide's exit, else R(Q_x)^n_x R(Q_y)^n_y for
                                 its n_x and n_y reflections (Q = 4 pi
                                 sin(grazing angle)/lambda).  Also weights the
-                                transmitted beam.  Runs with a guide tally
-                                with atomics like attenuated ones; the
+                                transmitted beam.  Runs with a guide take
+                                the tallies attenuated ones take; the
                                 batched launch and the surrogate mode refuse
                                 a guide                                     */
 } sans_params;

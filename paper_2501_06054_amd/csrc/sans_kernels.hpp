@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const TraceArgs a, LdsLayout l
 // (plain stores), summed afterwards by k_reduce_partials.
 constexpr int kHistBlock = 1024;
 
-template <int KIND, int MODE>
+template <int KIND, int MODE, bool ATT = false>
 __global__ __launch_bounds__(kHistBlock) void k_trace_hist(const TraceArgs a, LdsLayout lay,
                                                            double* partial)
 {
@@ -133,8 +133,8 @@ __global__ __launch_bounds__(kHistBlock) void k_trace_hist(const TraceArgs a, Ld
     __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += stride) {
-        const Event ev = trace_neutron<KIND, MODE>(loop_args(kernel_args()), a.first + j, lp.tsize, lp.tnorm,
-                                                   lp.lq);
+        const Event ev = trace_neutron<KIND, MODE, ATT>(loop_args(kernel_args()), a.first + j, lp.tsize,
+                                                        lp.tnorm, lp.lq);
         if (ev.pixel >= 0)
             __hip_atomic_fetch_add(lp.hist + ev.pixel, (double)ev.w, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kHistBlock) void k_trace_hist(const TraceArgs a, Ld
 constexpr int kEmitBlock = 256;
 constexpr int kMaxTiles = 64;
 
-template <int KIND, int MODE>
+template <int KIND, int MODE, bool ATT = false>
 __global__ __launch_bounds__(kEmitBlock) void k_emit(const TraceArgs a, LdsLayout lay, uint2* buckets,
                                                      unsigned* seg_count, unsigned capw, int tile_pixels,
                                                      int ntiles)
@@ -171,8 +171,8 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const TraceArgs a, LdsLayou
         unsigned local = 0;
         float w = 0.0f;
         if (j < a.n) {
-            const Event ev = trace_neutron<KIND, MODE>(loop_args(kernel_args()), a.first + j, lp.tsize,
-                                                       lp.tnorm, lp.lq);
+            const Event ev = trace_neutron<KIND, MODE, ATT>(loop_args(kernel_args()), a.first + j, lp.tsize,
+                                                            lp.tnorm, lp.lq);
             if (ev.pixel >= 0) {
                 t = ev.pixel / tile_pixels;
                 local = (unsigned)(ev.pixel - t * tile_pixels);
@@ -450,8 +450,8 @@ using PqFn = void (*)(const TraceArgs, LdsLayout, const float*, const float*, in
 // (unattenuated Monte Carlo runs) do not.
 struct KindFns {
     TraceFn trace[2][2];
-    HistFn hist[2];
-    EmitFn emit[2];
+    HistFn hist[3];        // [0] Monte Carlo, [1] exact average, [2] Monte Carlo with attenuation / guide
+    EmitFn emit[3];
     DebugFn debug[2][2];   // [mode][attenuation compiled in]
     PqFn pq;
 };
@@ -466,8 +466,10 @@ void fill_kind(KindFns* t)
     f.trace[1][1] = k_trace<K, 1, SANS_TALLY_XCD>;
     f.hist[0] = k_trace_hist<K, 0>;
     f.hist[1] = k_trace_hist<K, 1>;
+    f.hist[2] = k_trace_hist<K, 0, true>;
     f.emit[0] = k_emit<K, 0>;
     f.emit[1] = k_emit<K, 1>;
+    f.emit[2] = k_emit<K, 0, true>;
     // the per-neutron kernel compiles the same instance of the neutron code as
     // the kernels that tally: the attenuation only where those carry it
     f.debug[0][0] = k_debug<K, 0, false>;

@@ -350,15 +350,20 @@ TraceFn pick_trace(int kind, int mode, int tally)
                             : nullptr;
 }
 
-HistFn pick_hist(int kind, int mode)
+// att: the Monte Carlo instance with the attenuation and the guide compiled in
+HistFn pick_hist(int kind, int mode, bool att)
 {
-    return known_kind(kind) ? kind_table()[kind].hist[mode == 0 ? 0 : 1] : nullptr;
+    return known_kind(kind) ? kind_table()[kind].hist[mode != 0 ? 1 : att ? 2 : 0] : nullptr;
 }
 
-EmitFn pick_emit(int kind, int mode)
+EmitFn pick_emit(int kind, int mode, bool att)
 {
-    return known_kind(kind) ? kind_table()[kind].emit[mode == 0 ? 0 : 1] : nullptr;
+    return known_kind(kind) ? kind_table()[kind].emit[mode != 0 ? 1 : att ? 2 : 0] : nullptr;
 }
+
+// Runs that need the attenuation or the guide (only some kernel instances
+// carry them).
+bool needs_instrument(const sans_params& p) { return p.mu_att > 0.0 || p.guide[0] > 0.0; }
 
 DebugFn pick_debug(int kind, int mode, bool att)
 {
@@ -1546,9 +1551,9 @@ int choose_tally(const sans_model_s* m, bool extras)
 {
     int t = m->p.tally;
     // the optional sum-of-squares and count outputs use the atomic path, and
-    // so do runs with attenuation or a guide (only the atomic-tally kernels
-    // carry them)
-    if (extras || m->p.mu_att > 0.0 || m->p.guide[0] > 0.0)
+    // so do exact-average runs with attenuation or a guide (their histogram
+    // and binned kernels are compiled without them)
+    if (extras || (needs_instrument(m->p) && m->p.mode != SANS_MODE_MC))
         return t == SANS_TALLY_XCD ? SANS_TALLY_XCD : SANS_TALLY_GLOBAL;
     // the exact average spends thousands of operations per tallied neutron:
     // plain atomics cost nothing there, and the workgroup histogram's LDS
@@ -1888,7 +1893,7 @@ int trace_scattered(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, u
     if (tally == SANS_TALLY_LDS) {
         const LdsLayout lay = layout(m, true);
         const size_t shmem = lds_bytes(lay);
-        HistFn fn = pick_hist(m->p.kind, m->p.mode);
+        HistFn fn = pick_hist(m->p.kind, m->p.mode, needs_instrument(m->p));
         int rc = set_lds_limit((const void*)fn, shmem);
         if (rc) return rc;
         const uint64_t blocks_needed = (n + kHistBlock - 1) / kHistBlock;
@@ -1927,7 +1932,7 @@ int trace_scattered(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, u
         if ((rc = launch_fill(m->d_partial, (size_t)ntiles * slices * tile_pixels, s))) return rc;
         const LdsLayout lay = layout(m, false);
         const size_t shmem = lds_bytes(lay);
-        EmitFn efn = pick_emit(m->p.kind, m->p.mode);
+        EmitFn efn = pick_emit(m->p.kind, m->p.mode, needs_instrument(m->p));
         if ((rc = set_lds_limit((const void*)efn, shmem))) return rc;
         if ((rc = set_lds_limit((const void*)k_bin_accumulate, sizeof(double) * tile_pixels))) return rc;
         for (uint64_t c0 = 0; c0 < n; c0 += chunk) {
