@@ -131,7 +131,8 @@ def lib():
         for f in ("orc_normal_quantile",):
             getattr(L, f).argtypes = [d]
             getattr(L, f).restype = d
-        for f in ("orc_schulz_quantile", "orc_truncnorm_quantile", "orc_gamma_p", "orc_py_g_over_x_direct"):
+        for f in ("orc_schulz_quantile", "orc_truncnorm_quantile", "orc_gamma_p", "orc_py_g_over_x_direct",
+                  "orc_gamma_q", "orc_schulz_quantile_upper"):
             getattr(L, f).argtypes = [d, d]
             getattr(L, f).restype = d
         for f in ("orc_sph", "orc_lambda1", "orc_sinc"):
@@ -291,6 +292,20 @@ def size_moment(p: dict, k: int) -> float:
 
 def gamma_p(a: float, x: float) -> float:
     return lib().orc_gamma_p(a, x)
+
+
+def gamma_q(a: float, x: float) -> float:
+    return lib().orc_gamma_q(a, x)
+
+
+def schulz_quantile_upper(v: float, p: float) -> float:
+    """The Schulz size whose upper tail holds probability v."""
+    return lib().orc_schulz_quantile_upper(v, p)
+
+
+def table_dt(M: int) -> float:
+    """Knot spacing in t = -ln(2 min(u, 1 - u)) of an M-knot table."""
+    return 32.0 * np.log(2.0) / (M // 2 - 1)
 
 
 def table_normal(M: int) -> np.ndarray:

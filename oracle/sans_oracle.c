@@ -235,6 +235,32 @@ double orc_gamma_p(double a, double x)
     return 1.0 - exp(lpre) * h;
 }
 
+/* Regularised upper incomplete gamma Q(a, x) = 1 - P(a, x), computed
+ * directly (Legendre's continued fraction) where it is small, so that the
+ * far upper tail keeps its relative precision. */
+double orc_gamma_q(double a, double x)
+{
+    if (x <= 0.0) return 1.0;
+    if (x < a + 1.0) return 1.0 - orc_gamma_p(a, x);
+    double lpre = a * log(x) - x - lgamma(a);
+    const double tiny = 1e-300;
+    double b = x + 1.0 - a;
+    double c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int n = 1; n < 1000000; ++n) {
+        double an = -n * (n - a);
+        b += 2.0;
+        d = an * d + b;
+        if (fabs(d) < tiny) d = tiny;
+        c = b + an / c;
+        if (fabs(c) < tiny) c = tiny;
+        d = 1.0 / d;
+        double del = d * c;
+        h *= del;
+        if (fabs(del - 1.0) < 1e-16) break;
+    }
+    return exp(lpre) * h;
+}
+
 /* Schulz distribution of the relative size y (mean 1, relative width p):
  * y ~ Gamma(shape a = 1/p^2, scale 1/a), i.e. z = 1/p^2 - 1 in the usual
  * Schulz notation.  Quantile by bisection of P(a, a*y) = u. */
@@ -251,6 +277,21 @@ double orc_schulz_quantile(double u, double p)
     return 0.5 * (lo + hi);
 }
 
+/* The Schulz size whose upper tail holds probability v: bisection of
+ * Q(a, a*y) = v. */
+double orc_schulz_quantile_upper(double v, double p)
+{
+    double a = 1.0 / (p * p);
+    double lo = 0.0, hi = 1.0;
+    while (orc_gamma_q(a, a * hi) > v) hi *= 2.0;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (orc_gamma_q(a, a * mid) > v) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* The paper's size distribution (Methods, "Polydispersity and orientational
  * distributions", Eq. (8)): y ~ N(1, p^2), redrawn until positive, i.e. the
  * normal distribution restricted to y > 0.  Its quantile maps u into the
@@ -262,20 +303,46 @@ double orc_truncnorm_quantile(double u, double p)
     return 1.0 + p * orc_normal_quantile(c0 + u * (1.0 - c0));
 }
 
-/* Inverse-CDF table: knots y_k = F^-1((k + 1/2)/M), k = 0 .. M-1. */
+/* Inverse-CDF tables.  The knots are equally spaced in
+ * t = -ln(2 min(u, 1 - u)), which places them densely in both tails: with
+ * H = M/2 and dt = 32 ln 2 / (H - 1) (t = 32 ln 2 is the farthest tail a
+ * 32-bit uniform reaches, u = 2^-33), knot j < H is F^-1(e^(-j dt)/2) (the
+ * lower half, from the median down) and knot H + j is F^-1(1 - e^(-j dt)/2)
+ * (the upper half, from the median up); the upper half is computed from the
+ * upper tail's probability, so the far tail keeps its precision. */
+static double table_dt(int32_t M) { return 32.0 * log(2.0) / (M / 2 - 1); }
+
 void orc_table_normal(int32_t M, double* knots)
 {
-    for (int k = 0; k < M; ++k) knots[k] = orc_normal_quantile((k + 0.5) / M);
+    const int H = M / 2;
+    for (int j = 0; j < H; ++j) {
+        double q = orc_normal_quantile(0.5 * exp(-j * table_dt(M)));
+        knots[j] = q;
+        knots[H + j] = -q;
+    }
 }
 
 void orc_table_schulz(int32_t M, double p, double* knots)
 {
-    for (int k = 0; k < M; ++k) knots[k] = orc_schulz_quantile((k + 0.5) / M, p);
+    const int H = M / 2;
+    for (int j = 0; j < H; ++j) {
+        double v = 0.5 * exp(-j * table_dt(M));
+        knots[j] = orc_schulz_quantile(v, p);
+        knots[H + j] = orc_schulz_quantile_upper(v, p);
+    }
 }
 
 void orc_table_truncnorm(int32_t M, double p, double* knots)
 {
-    for (int k = 0; k < M; ++k) knots[k] = orc_truncnorm_quantile((k + 0.5) / M, p);
+    /* upper tail: 1 - u = v, so c0 + u (1 - c0) = 1 - v (1 - c0) and, by the
+       symmetry of the normal, y = 1 - p Phi^-1(v (1 - c0)) */
+    const int H = M / 2;
+    double c0 = normal_cdf(-1.0 / p);
+    for (int j = 0; j < H; ++j) {
+        double v = 0.5 * exp(-j * table_dt(M));
+        knots[j] = orc_truncnorm_quantile(v, p);
+        knots[H + j] = 1.0 - p * orc_normal_quantile(v * (1.0 - c0));
+    }
 }
 
 /* The size table of a parameter set (Schulz or positive Gaussian). */
@@ -285,18 +352,20 @@ static void size_table(const orc_params* p, double* knots)
     else orc_table_schulz(p->table_size, p->poly, knots);
 }
 
-/* Table lookup: s = u M - 1/2, k = clamp(floor(s), 0, M-2), linear
- * interpolation between knots k and k+1 (linear extrapolation in the two end
- * half-cells). */
+/* Table lookup: t = -ln(2 min(u, 1 - u)), s = t/dt, j = min(floor(s),
+ * H - 2), linear interpolation in t between knots j and j + 1 of the half
+ * that u falls in (u < 1/2 the lower half, else the upper one). */
 double orc_table_lookup(const double* knots, int32_t M, double u)
 {
-    double s = u * M - 0.5;
-    double fk = floor(s);
-    if (fk < 0.0) fk = 0.0;
-    if (fk > M - 2) fk = M - 2;
-    int k = (int)fk;
-    double f = s - fk;
-    return knots[k] + f * (knots[k + 1] - knots[k]);
+    const int H = M / 2;
+    const double* half = u < 0.5 ? knots : knots + H;
+    double t = -log(2.0 * (u < 0.5 ? u : 1.0 - u));
+    double s = t / table_dt(M);
+    double fj = floor(s);
+    if (fj > H - 2) fj = H - 2;
+    int j = (int)fj;
+    double f = s - fj;
+    return half[j] + f * (half[j + 1] - half[j]);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -67,27 +67,88 @@ def test_schulz_quantile_vs_library(orc):
             assert orc.schulz_quantile(u, p) == pytest.approx(ref, rel=1e-10)
 
 
+def test_gamma_q_vs_library(orc):
+    for a in [0.5, 2.0, 11.1, 25.0, 400.0]:
+        for x in [0.7 * a, 1.3 * a, 2.5 * a, 4.0 * a + 30.0]:
+            assert orc.gamma_q(a, x) == pytest.approx(sp.gammaincc(a, x), rel=1e-11, abs=1e-300)
+
+
+def test_table_knots_vs_library(orc):
+    """Knot j of the lower half is F^-1(e^(-j dt)/2), knot H + j of the upper
+    half F^-1(1 - e^(-j dt)/2), dt = 32 ln 2 / (H - 1): against SciPy's
+    normal, Gamma and truncated-normal quantiles, upper tails through their
+    survival functions."""
+    from scipy import stats
+    M = 512
+    H = M // 2
+    dt = orc.table_dt(M)
+    assert dt == pytest.approx(32 * math.log(2) / (H - 1), rel=1e-15)
+    js = np.array([0, 1, 7, 60, 170, H - 1])
+    v = 0.5 * np.exp(-js * dt)
+    tn = orc.table_normal(M)
+    np.testing.assert_allclose(tn[js], sp.ndtri(v), rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(tn[H + js], -sp.ndtri(v), rtol=1e-11, atol=1e-13)
+    for p in (0.1, 0.3, 0.7):
+        a = 1.0 / p**2
+        g = stats.gamma(a, scale=1.0 / a)
+        ts = orc.table_schulz(M, p)
+        np.testing.assert_allclose(ts[js], g.ppf(v), rtol=1e-9)
+        np.testing.assert_allclose(ts[H + js], g.isf(v), rtol=1e-9)
+        tr = stats.truncnorm(-1.0 / p, np.inf, loc=1.0, scale=p)
+        tt = orc.table_truncnorm(M, p)
+        np.testing.assert_allclose(tt[js], tr.ppf(v), rtol=1e-9)
+        np.testing.assert_allclose(tt[H + js], tr.isf(v), rtol=1e-8)
+
+
 def test_table_lookup_interpolates_knots(orc):
     M = 64
+    H = M // 2
+    dt = orc.table_dt(M)
     knots = orc.table_normal(M)
-    for k in [0, 5, 31, 63]:
-        assert orc.table_lookup(knots, (k + 0.5) / M) == pytest.approx(knots[k], abs=1e-15)
-    # halfway between two knots -> their mean; linear extrapolation at the ends
-    assert orc.table_lookup(knots, 10.0 / M) == pytest.approx(0.5 * (knots[9] + knots[10]))
-    assert orc.table_lookup(knots, 0.0) == pytest.approx(knots[0] - 0.5 * (knots[1] - knots[0]))
-    assert orc.table_lookup(knots, 1.0) == pytest.approx(knots[-1] + 0.5 * (knots[-1] - knots[-2]))
+    for j in [0, 5, 17, H - 1]:
+        v = 0.5 * math.exp(-j * dt)
+        assert orc.table_lookup(knots, v) == pytest.approx(knots[j], rel=1e-13, abs=1e-14)
+        assert orc.table_lookup(knots, 1.0 - v) == pytest.approx(knots[H + j], rel=1e-9, abs=1e-12)
+    # halfway in t between two knots -> their mean; the median from either half
+    v = 0.5 * math.exp(-9.5 * dt)
+    assert orc.table_lookup(knots, v) == pytest.approx(0.5 * (knots[9] + knots[10]), rel=1e-12)
+    assert orc.table_lookup(knots, 0.5) == knots[H] == pytest.approx(knots[0], abs=1e-15)
 
 
-def test_schulz_table_moments(orc):
-    # integrate the lookup over u in (0, 1): the moments of the tabulated
-    # distribution are the Schulz closed-form moments up to the tails
-    M = 4096
-    knots = orc.table_schulz(M, 0.2)
-    u = (np.arange(200000) + 0.5) / 200000
-    y = np.array([orc.table_lookup(knots, x) for x in u[::10]])
-    assert np.mean(y) == pytest.approx(1.0, abs=2e-4)
-    assert np.mean(y**3) == pytest.approx(SV["schulz_m3_p0.2"], rel=3e-4)
-    assert np.mean(y**6) == pytest.approx(SV["schulz_m6_p0.2"], rel=2e-3)
+def _sampler_moment(orc, knots, k):
+    """E[y^k] for u uniform on (0, 1) mapped through the lookup: in t each half
+    is piecewise linear, u = e^(-t)/2, du = e^(-t)/2 dt; 16-point Gauss-Legendre
+    on every knot interval (exact up to rounding for these smooth pieces),
+    to t = 32 ln 2 (a 32-bit uniform reaches no farther)."""
+    M = len(knots)
+    H = M // 2
+    dt = orc.table_dt(M)
+    gx, gw = np.polynomial.legendre.leggauss(16)
+    tot = 0.0
+    for half in (knots[:H], knots[H:]):
+        for j in range(H - 1):
+            t = (j + 0.5 * (gx + 1.0)) * dt
+            y = half[j] + (t / dt - j) * (half[j + 1] - half[j])
+            tot += np.sum(0.5 * dt * gw * np.maximum(y, 0.0) ** k * 0.5 * np.exp(-t))
+    return tot
+
+
+@pytest.mark.parametrize("p", [0.1, 0.2, 0.3, 0.5])
+def test_size_table_moments_match_the_distribution(orc, p):
+    """The table sampler reproduces the moments the weight divides by: E[y],
+    E[y^3] and E[y^6] of the tabulated distribution (the lookup integrated
+    over u) against the Schulz closed form prod_{i<k} (a + i)/a and the
+    truncated normal's moments, within 1e-5 at M = 4096 (the tails, which
+    carry most of E[y^6], are tabulated by their own probability)."""
+    from scipy import stats
+    a = 1.0 / p**2
+    ts = orc.table_schulz(4096, p)
+    tr = stats.truncnorm(-1.0 / p, np.inf, loc=1.0, scale=p)
+    tt = orc.table_truncnorm(4096, p)
+    for k in (1, 3, 6):
+        exact = float(np.prod([(a + i) / a for i in range(k)]))
+        assert _sampler_moment(orc, ts, k) == pytest.approx(exact, rel=1e-5)
+        assert _sampler_moment(orc, tt, k) == pytest.approx(tr.moment(k), rel=1e-5)
 
 
 # ----------------------------------------------------------------- shapes
