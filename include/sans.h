@@ -402,7 +402,7 @@ typedef struct {
                                 poly_kind); 0 = monodisperse                   */
     int32_t poly_mask;       /* bit k set: size[k] is multiplied by y (the core-
                                 shell shell never is)                          */
-    int32_t table_size;      /* knots of the inverse-CDF tables (64..8192)     */
+    int32_t table_size;      /* knots of the inverse-CDF tables (even, 64..8192) */
     double orient_mean[3];   /* theta, phi, Psi                                */
     double orient_sigma[3];  /* Gaussian spreads (SANS_ORIENT_GAUSSIAN)        */
     double src_w, src_h, src_z;
@@ -476,8 +476,12 @@ typedef struct {
 
 typedef struct sans_model_s* sans_model_t;
 
-/* Validates p, builds the inverse-CDF tables (standard normal and Schulz
- * quantiles at (k + 1/2)/M, FP64, staged in LDS by the kernels)
+/* Validates p, builds the inverse-CDF tables (standard normal, Schulz or
+ * positive-Gaussian quantiles, FP64, staged in LDS by the kernels; M knots
+ * equally spaced in t = -ln(2 min(u, 1 - u)) with step 32 ln 2 / (M/2 - 1):
+ * knot j < M/2 at u = e^(-j dt)/2, knot M/2 + j at u = 1 - e^(-j dt)/2, so
+ * that both tails, which carry the high size moments the weight divides by,
+ * are tabulated to the farthest probability a 32-bit uniform reaches)
  * and the model constants.  *out receives an opaque handle owning its device
  * buffers.  Errors: SANS_E_INVALID_ARG (null pointers, wrong abi_version, a
  * size <= 0, a cap radius below the cylinder radius, negative widths or

@@ -539,15 +539,24 @@ __device__ __forceinline__ float struct_factor(const TraceArgs& a, float q)
     return rcpf(inv);
 }
 
-// Linear interpolation in an FP64 inverse-CDF table (knots at (k + 1/2)/M).
+// Inverse-CDF lookup in an FP64 table whose knots are equally spaced in
+// t = -ln(2 min(u, 1 - u)) with step 32 ln 2 / (M/2 - 1): the lower half
+// (knots 0 .. M/2 - 1, from the median down) for u < 1/2, else the upper half
+// (from the median up), linear in t.  t and the interpolation fraction are
+// formed in FP32: the lookup is continuous across knots, so their rounding
+// moves y by parts in 1e7 of one knot interval.
 __device__ __forceinline__ double table_lerp(const double* tab, int M, double u)
 {
-    const double s = __builtin_fma(u, (double)M, -0.5);
-    double fk = floor(s);
-    fk = fmin(fmax(fk, 0.0), (double)(M - 2));
-    const int k = (int)fk;
-    const double f = s - fk;
-    const double y0 = tab[k], y1 = tab[k + 1];
+    const int H = M >> 1;
+    const bool up = u >= 0.5;
+    const double v = up ? 1.0 - u : u;
+    const float t = -0.693147181f * log2f((float)(2.0 * v));
+    const float s = t * ((float)(H - 1) * 0.0450842200f);   // t / dt
+    const float fj = fminf(fmaxf(floorf(s), 0.0f), (float)(H - 2));
+    const int j = (int)fj;
+    const double f = (double)(s - fj);
+    const double* half = up ? tab + H : tab;
+    const double y0 = half[j], y1 = half[j + 1];
     return __builtin_fma(f, y1 - y0, y0);
 }
 

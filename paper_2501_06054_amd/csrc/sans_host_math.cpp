@@ -220,6 +220,30 @@ double positive_normal_quantile(double u, double p)
     return 1.0 + p * normal_quantile(c0 + u * (1.0 - c0));
 }
 
+double table_tail(int j, int M) { return 0.5 * std::exp(-j * (32.0 * std::log(2.0) / (M / 2 - 1))); }
+
+void normal_table(int M, double* out)
+{
+    const int H = M / 2;
+    for (int j = 0; j < H; ++j) {
+        out[j] = normal_quantile(table_tail(j, M));
+        out[H + j] = -out[j];
+    }
+}
+
+// Upper half: 1 - u = v, so c0 + u (1 - c0) = 1 - v (1 - c0) and, the normal
+// being symmetric, y = 1 - p Phi^-1(v (1 - c0)).
+void positive_normal_table(int M, double p, double* out)
+{
+    const int H = M / 2;
+    const double c0 = 0.5 * std::erfc(1.0 / (p * std::sqrt(2.0)));
+    for (int j = 0; j < H; ++j) {
+        const double v = table_tail(j, M);
+        out[j] = positive_normal_quantile(v, p);
+        out[H + j] = 1.0 - p * normal_quantile(v * (1.0 - c0));
+    }
+}
+
 // E[y^k] of that distribution by composite Gauss-Legendre quadrature of
 // y^k exp(-(y-1)^2 / 2p^2) over [max(0, 1 - 12p), 1 + 12p] (8 panels of 16
 // nodes), divided by the same quadrature of the density.

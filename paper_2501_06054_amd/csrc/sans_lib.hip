@@ -222,12 +222,15 @@ __global__ void k_sum_replicas(double* det, double* rep, int npix, int accumulat
 
 
 // ------------------------------------------------------------------ Schulz tables (FP64)
-// Quantiles y_k = F^-1((k + 1/2)/M) of the Schulz distribution (Gamma with
-// shape a = 1/p^2 and mean 1): the CDF is tabulated by integrating the density
-// over kSchulzPanels panels (16-point Gauss-Legendre each, prefix-summed in
-// LDS); each quantile is then refined inside its panel by safeguarded Newton
-// steps on C(y_j) + int_{y_j}^{y} pdf - u = 0.  One workgroup per table.
-constexpr int kSchulzPanels = 4096;
+// Knots of the Schulz distribution (Gamma with shape a = 1/p^2 and mean 1)
+// in the tables' layout: knot j < M/2 at the lower-tail probability
+// v_j = e^(-j dt)/2, knot M/2 + j at the upper-tail probability v_j.  The
+// density is integrated over kSchulzPanels panels (16-point Gauss-Legendre
+// each) and summed in LDS from the bottom (the CDF) and from the top (the
+// upper tail, so that tail probabilities down to 1e-10 keep their relative
+// precision); each knot is then refined inside its panel by safeguarded
+// Newton steps.  One workgroup per table.
+constexpr int kSchulzPanels = 2048;
 constexpr int kSchulzBlock = 256;
 
 struct SchulzJob {
@@ -236,7 +239,7 @@ struct SchulzJob {
 };
 
 // Gauss-Legendre nodes on [-1, 1]: 16 points for the panels of the CDF, 4
-// for the Newton steps inside one panel (a panel is about 1/4096 of the
+// for the Newton steps inside one panel (a panel is about 1/2048 of the
 // support: the 4-point rule is exact to rounding there).
 struct GL16 {
     double x[16], w[16];
@@ -267,21 +270,9 @@ __device__ __forceinline__ double pdf_integral4(double lo, double hi, double a, 
     return h * s;
 }
 
-__global__ __launch_bounds__(kSchulzBlock) void k_schulz_tables(const SchulzJob* jobs, int M,
-                                                                double* tables, const GL16 g)
+// Exclusive scan of one value per thread across the block (in part[]).
+__device__ __forceinline__ void block_offsets(double* part)
 {
-    __shared__ double cdf[kSchulzPanels + 1];
-    __shared__ double part[kSchulzBlock];
-    const SchulzJob jb = jobs[blockIdx.x];
-    const double dy = jb.ymax / kSchulzPanels;
-    constexpr int per = kSchulzPanels / kSchulzBlock;
-    const int j0 = threadIdx.x * per;
-    double acc = 0.0;
-    for (int k = 0; k < per; ++k) {
-        acc += pdf_integral((j0 + k) * dy, (j0 + k + 1) * dy, jb.a, jb.lnorm, g);
-        cdf[j0 + k + 1] = acc;
-    }
-    part[threadIdx.x] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
         double r = 0.0;
@@ -290,24 +281,65 @@ __global__ __launch_bounds__(kSchulzBlock) void k_schulz_tables(const SchulzJob*
             part[t] = r;
             r += v;
         }
-        cdf[0] = 0.0;
     }
     __syncthreads();
+}
+
+__global__ __launch_bounds__(kSchulzBlock) void k_schulz_tables(const SchulzJob* jobs, int M,
+                                                                double* tables, const GL16 g)
+{
+    __shared__ double cdf[kSchulzPanels + 1];   // integral over [0, j dy]
+    __shared__ double sdf[kSchulzPanels + 1];   // integral over [j dy, ymax]
+    __shared__ double part[kSchulzBlock];
+    const SchulzJob jb = jobs[blockIdx.x];
+    const double dy = jb.ymax / kSchulzPanels;
+    constexpr int per = kSchulzPanels / kSchulzBlock;
+    const int j0 = threadIdx.x * per;
+    double pan[per];
+    double acc = 0.0;
+    for (int k = 0; k < per; ++k) {
+        pan[k] = pdf_integral((j0 + k) * dy, (j0 + k + 1) * dy, jb.a, jb.lnorm, g);
+        acc += pan[k];
+        cdf[j0 + k + 1] = acc;
+    }
+    part[threadIdx.x] = acc;
+    block_offsets(part);
     for (int k = 0; k < per; ++k) cdf[j0 + k + 1] += part[threadIdx.x];
+    if (threadIdx.x == 0) cdf[0] = 0.0;
+    // the same from the top: thread t holds panels j0 .. j0 + per - 1, whose
+    // tails are summed downwards, offset by the threads above it
+    __syncthreads();
+    double up = 0.0;
+    for (int k = per - 1; k >= 0; --k) {
+        up += pan[k];
+        sdf[j0 + k] = up;
+    }
+    part[kSchulzBlock - 1 - threadIdx.x] = up;
+    block_offsets(part);
+    for (int k = 0; k < per; ++k) sdf[j0 + k] += part[kSchulzBlock - 1 - threadIdx.x];
+    if (threadIdx.x == 0) sdf[kSchulzPanels] = 0.0;
     __syncthreads();
     const double total = cdf[kSchulzPanels];
+    const int H = M / 2;
+    const double dt = 32.0 * 0.69314718055994530942 / (H - 1);
     for (int k = threadIdx.x; k < M; k += blockDim.x) {
-        const double u = (k + 0.5) / M * total;
+        const bool upper = k >= H;
+        const double v = 0.5 * exp(-(upper ? k - H : k) * dt) * total;
+        // the panel holding the knot: cdf[j] <= v < cdf[j+1] (lower), or
+        // sdf[j+1] <= v < sdf[j] (upper)
         int lo = 0, hi = kSchulzPanels;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (cdf[mid] <= u) lo = mid; else hi = mid;
+            if (upper ? sdf[mid] > v : cdf[mid] <= v) lo = mid; else hi = mid;
         }
         const int j = lo;
         double ylo = j * dy, yhi = (j + 1) * dy;
-        double y = ylo + (u - cdf[j]) / fmax(cdf[j + 1] - cdf[j], 1e-300) * dy;
+        double y = upper ? ylo + (sdf[j] - v) / fmax(sdf[j] - sdf[j + 1], 1e-300) * dy
+                         : ylo + (v - cdf[j]) / fmax(cdf[j + 1] - cdf[j], 1e-300) * dy;
         for (int it = 0; it < 60; ++it) {
-            const double gval = cdf[j] + pdf_integral4(j * dy, y, jb.a, jb.lnorm, g) - u;
+            // increasing in y for both halves: the mass below y minus its target
+            const double gval = upper ? v - (sdf[j + 1] + pdf_integral4(y, (j + 1) * dy, jb.a, jb.lnorm, g))
+                                      : cdf[j] + pdf_integral4(j * dy, y, jb.a, jb.lnorm, g) - v;
             if (gval > 0.0) yhi = y; else ylo = y;
             const double f = schulz_pdf_d(y, jb.a, jb.lnorm);
             double yn = f > 0.0 ? y - gval / f : 0.5 * (ylo + yhi);
@@ -955,8 +987,8 @@ int validate(const sans_params* p)
         if (p->poly_kind != SANS_POLY_GAUSSIAN)
             return fail(SANS_E_UNSUPPORTED, "poly_sep: the positive Gaussian (SANS_POLY_GAUSSIAN) only");
     }
-    if (p->table_size < 64 || p->table_size > 8192)
-        return fail(SANS_E_INVALID_ARG, "table_size must be in 64..8192");
+    if (p->table_size < 64 || p->table_size > 8192 || (p->table_size & 1))
+        return fail(SANS_E_INVALID_ARG, "table_size must be even and in 64..8192");
     for (int k = 0; k < 3; ++k) {
         if (!finite(p->orient_mean[k])) return fail(SANS_E_INVALID_ARG, "orient_mean must be finite");
         if (!(p->orient_sigma[k] >= 0.0) || !finite(p->orient_sigma[k]))
@@ -1374,8 +1406,7 @@ int configure(sans_model_s* m, const sans_params* p)
             if (p->poly_kind == SANS_POLY_GAUSSIAN) {
                 // closed-form quantile: built on the host
                 m->h_tab_size.resize(p->table_size);
-                for (int k = 0; k < p->table_size; ++k)
-                    m->h_tab_size[k] = host::positive_normal_quantile((k + 0.5) / p->table_size, p->poly);
+                host::positive_normal_table(p->table_size, p->poly, m->h_tab_size.data());
                 HIP_TRY(hipMemcpy(m->d_tab_size, m->h_tab_size.data(), sizeof(double) * p->table_size,
                                   hipMemcpyHostToDevice));
             } else {
@@ -1393,8 +1424,7 @@ int configure(sans_model_s* m, const sans_params* p)
     if (need_norm) {
         if (!norm_same) {
             m->h_tab_norm.resize(p->table_size);
-            for (int k = 0; k < p->table_size; ++k)
-                m->h_tab_norm[k] = host::normal_quantile((k + 0.5) / p->table_size);
+            host::normal_table(p->table_size, m->h_tab_norm.data());
             if (m->d_tab_norm) HIP_TRY(hipFree(m->d_tab_norm));
             m->d_tab_norm = nullptr;
             HIP_TRY(hipMalloc(&m->d_tab_norm, sizeof(double) * p->table_size));
@@ -1409,9 +1439,7 @@ int configure(sans_model_s* m, const sans_params* p)
         const int M = p->table_size;
         m->h_tab_sep.assign((size_t)3 * M, 1.0);
         for (int k = 0; k < 3; ++k)
-            if (a.sep_on[k])
-                for (int j = 0; j < M; ++j)
-                    m->h_tab_sep[(size_t)k * M + j] = host::positive_normal_quantile((j + 0.5) / M, p->poly_sep[k]);
+            if (a.sep_on[k]) host::positive_normal_table(M, p->poly_sep[k], m->h_tab_sep.data() + (size_t)k * M);
         if (m->d_tab_sep) HIP_TRY(hipFree(m->d_tab_sep));
         m->d_tab_sep = nullptr;
         HIP_TRY(hipMalloc(&m->d_tab_sep, sizeof(double) * 3 * M));
@@ -2532,7 +2560,7 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
     }
     if (any_norm && c.norm_M != M) {
         std::vector<double> t(M);
-        for (int k = 0; k < M; ++k) t[k] = host::normal_quantile((k + 0.5) / M);
+        host::normal_table(M, t.data());
         if (c.d_norm) HIP_TRY(hipFree(c.d_norm));
         c.d_norm = nullptr;
         c.norm_M = 0;
@@ -2549,7 +2577,9 @@ int sans_trace_batch(int n_exp, const sans_params* p, const uint64_t* n_neutrons
         if (p[e].poly > 0.0 && p[e].poly_kind == SANS_POLY_GAUSSIAN) {
             // closed-form quantiles, built on the host (after the Schulz slots)
             exps[e].tab_size = c.d_tables + (n_schulz + host_tabs.size() / M) * (size_t)M;
-            for (int k = 0; k < M; ++k) host_tabs.push_back(host::positive_normal_quantile((k + 0.5) / M, p[e].poly));
+            const size_t off = host_tabs.size();
+            host_tabs.resize(off + M);
+            host::positive_normal_table(M, p[e].poly, host_tabs.data() + off);
         } else if (p[e].poly > 0.0) {
             exps[e].tab_size = c.d_tables + jobs.size() * (size_t)M;
             jobs.push_back(schulz_job(p[e].poly, (unsigned long long)(jobs.size() * (size_t)M)));

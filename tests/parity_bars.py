@@ -68,13 +68,13 @@ def oracle_detector(p, n, seed, first=0):
 
 
 
-def oracle_detector_sparse(p, n, seed, exp_id=0, per_pixel=100.0):
+def oracle_detector_sparse(p, n, seed, exp_id=0, per_pixel=100.0, first=0):
     """The oracle's detector and the bar for it: the summed per-neutron bar
     when the hit pixels hold fewer than per_pixel neutrons on average (or the
     model needs it at any count), else the plain 1e-4 pixel bar."""
-    ref, _, cnt = oracle.trace(p, n, seed, exp_id=exp_id, nthreads=NTHREADS, with_count=True)
+    ref, _, cnt = oracle.trace(p, n, seed, first=first, exp_id=exp_id, nthreads=NTHREADS, with_count=True)
     nz = ref != 0
     if p["kind"] not in SUMMED_BAR and (not nz.any() or cnt[nz].mean() >= per_pixel):
         return ref, {}
-    _, w, _ = oracle.trace_debug(p, min(n, 100003), seed, exp_id=exp_id)
+    _, w, _ = oracle.trace_debug(p, min(n, 100003), seed, first=first, exp_id=exp_id)
     return ref, dict(count=cnt, w_max=float(np.max(np.abs(w))) if w.size else 0.0)

@@ -176,6 +176,7 @@ def test_unknown_poly_kind_rejected_without_gpu(S):
     # a deep, wide well drives 1/S(0) below zero
     (dict(kind="sphere", sq_phi=0.2, sq_radius=50.0, sq_kind="square_well", sq_extra=(3.0, 2.0)),
      "SANS_E_DOMAIN"),
+    (dict(kind="sphere", poly=0.1, table_size=1001), "SANS_E_INVALID_ARG"),
     (dict(kind="sphere", guide_len=-1.0), "SANS_E_INVALID_ARG"),
     (dict(kind="sphere", guide_len=5.0, guide_w=0.0), "SANS_E_INVALID_ARG"),
     (dict(kind="sphere", guide_len=5.0, guide_r0=1.2), "SANS_E_INVALID_ARG"),
