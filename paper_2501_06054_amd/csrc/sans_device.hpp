@@ -333,10 +333,39 @@ __device__ __forceinline__ float sph3j_series(float x)
     return __builtin_fmaf(r, x2, 1.0f);
 }
 
+// 3 j1(x)/x from its Taylor series to x^30, given x^2, for x <= kSphLongMax:
+// no branch and no square root.  FP32 Horner: absolute error below 1.4e-6
+// there (1 at x = 0), set by the cancellation of the alternating terms.
+constexpr float kSphLongMax = 8.0f;
+template <int M>
+__device__ __forceinline__ float sph_horner(float x2, float r)
+{
+    if constexpr (M < 0) {
+        return r;
+    } else {
+        return sph_horner<M - 1>(x2, __builtin_fmaf(r, x2, SphC<M>::v));
+    }
+}
+__device__ __forceinline__ float sph3j_long(float x2) { return sph_horner<14>(x2, SphC<15>::v); }
+
+// 3 j1(x)/x at an FP64 phase: the short series below 2, else the closed form
+// on the FP64 phase.  LONG: the long series up to x = kSphLong5 instead of
+// the short one up to 2, so that the lanes of a wave, which mostly lie below
+// 5, seldom split between the series and the closed form (both of which a
+// split wave runs).  Its absolute error there is below 2.3e-7, against 1e-8
+// for the other two forms: where an amplitude is a difference of nearly
+// equal spheres (vesicles, the shells of fractal aggregates) that error
+// would grow, so only the single sphere and the core-shell sphere take it.
+// The choice is the lane's own, so a neutron's weight does not depend on
+// which neutrons share its wave.
+constexpr float kSphLong5 = 5.0f;
+template <bool LONG = false>
 __device__ __forceinline__ float sph3j_d(double xd)
 {
     xd = fabs(xd);
     const float x = (float)xd;
+    if constexpr (LONG)
+        if (x <= kSphLong5) return sph3j_long(x * x);
     if (x < 2.0f) return sph3j_series(x);
     float s, c;
     sincos_phase(xd, s, c);
@@ -354,20 +383,6 @@ __device__ __forceinline__ float sph3j_f(float x)
     return 3.0f * __builtin_fmaf(-x, c, s) * (ix * ix * ix);
 }
 
-// 3 j1(x)/x from its Taylor series to x^30, given x^2, for x <= kSphLongMax:
-// no branch and no square root.  FP32 Horner: absolute error below 1.4e-6
-// there (1 at x = 0), set by the cancellation of the alternating terms.
-constexpr float kSphLongMax = 8.0f;
-template <int M>
-__device__ __forceinline__ float sph_horner(float x2, float r)
-{
-    if constexpr (M < 0) {
-        return r;
-    } else {
-        return sph_horner<M - 1>(x2, __builtin_fmaf(r, x2, SphC<M>::v));
-    }
-}
-__device__ __forceinline__ float sph3j_long(float x2) { return sph_horner<14>(x2, SphC<15>::v); }
 
 // 2 J1(x)/x (the cylinder's cross-section factor, Eq. (9)): Taylor series
 // below 3, the device library's j1f above.
@@ -1274,12 +1289,12 @@ __device__ __forceinline__ float amplitude_mc(const TraceArgs& a, double y, cons
     constexpr float k43pi = (float)(4.0 / 3.0 * kPi);
     if constexpr (KIND == kSphere) {
         const float r = (float)s[0];
-        return a.contrast * k43pi * r * r * r * sph3j_d(q * s[0]);
+        return a.contrast * k43pi * r * r * r * sph3j_d<true>(q * s[0]);
     } else if constexpr (KIND == kCoreShell) {
         const double ro_d = s[0] + a.shell;
         const float rc = (float)s[0], ro = (float)ro_d;
-        return a.cs_core * k43pi * rc * rc * rc * sph3j_d(q * s[0])
-             + a.cs_shell * k43pi * ro * ro * ro * sph3j_d(q * ro_d);
+        return a.cs_core * k43pi * rc * rc * rc * sph3j_d<true>(q * s[0])
+             + a.cs_shell * k43pi * ro * ro * ro * sph3j_d<true>(q * ro_d);
     } else if constexpr (KIND == kCylinder) {
         const double qab = sqrt(fmax(__builtin_fma(q, q, -qc * qc), 0.0));
         const float r = (float)s[0], len = (float)s[1];
