@@ -284,17 +284,20 @@ struct SurConst {
 // samples at a time, activations in registers); in-domain neutrons are
 // tallied with FP64 global atomics, the others queued for the exact pass.
 template <int KIND>
-__global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const mlp::bf16x8* __restrict__ pk,
-                                                      const __bf16* __restrict__ wts, const SurConst sc,
-                                                      double* det, unsigned long long* queue, unsigned* qcount)
+__global__ __launch_bounds__(sur::kSurBlock) void k_trace_sur(const TraceArgs a, const mlp::bf16x8* __restrict__ pk,
+                                                              const __bf16* __restrict__ wts, const SurConst sc,
+                                                              double* det, unsigned long long* queue,
+                                                              unsigned* qcount)
 {
-    __shared__ float xs_all[kBlock / 64][64 * mlp::kIn];
+    extern __shared__ __attribute__((aligned(16))) unsigned char sur_lds[];
+    mlp::bf16x8* wl = (mlp::bf16x8*)sur_lds;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float* xs = xs_all[wave];
-    const __amdgpu_buffer_rsrc_t rp = sur::make_rsrc(pk, (int)(16 * sur::kPackTotal));
+    float* xs = (float*)(sur_lds + sur::kSurLdsWeights) + wave * 64 * mlp::kIn;
     const __amdgpu_buffer_rsrc_t rw = sur::make_rsrc(wts, (int)(2 * sur::kWeightsPadded));
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < a.n; j0 += stride) {
+    const uint64_t stride = (uint64_t)gridDim.x * sur::kSurBlock;
+    // the loop bound is the workgroup's, so that every wave reaches the
+    // barriers of the staged layers together
+    for (uint64_t j0 = (uint64_t)blockIdx.x * sur::kSurBlock; j0 < a.n; j0 += stride) {
         const uint64_t j = j0 + threadIdx.x;
         const bool valid = j < a.n;
         Event ev{-1, 0.0f, 0.0f, 0.0f};
@@ -313,19 +316,15 @@ __global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const m
         xr[2] = sc.x2;
         xr[3] = sc.x3;
         xr[4] = xr[5] = xr[6] = xr[7] = 0.0f;
-        __syncthreads();
         float y = 0.0f;
 #pragma unroll 1
         for (int c = 0; c < 4; c += 2) {
-            // the weight loads must not be hoisted out of this loop (they
-            // would occupy hundreds of registers): opaque memory barrier
             asm volatile("" ::: "memory");
             float yc[2];
-            sur::forward32(rp, rw, xs, c, yc);
+            sur::forward32_lds(pk, wl, rw, xs, c, yc);
             if ((lane >> 4) == c) y = yc[0];
             if ((lane >> 4) == c + 1) y = yc[1];
         }
-        __syncthreads();
         if (in_dom) {
             const float t = __builtin_fmaf(ev.q * ev.q, sc.kref, 1.0f);
             const double w = (double)(ev.w * sc.f2_0 * __expf(y) * rcpf(t * t));
@@ -334,6 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_trace_sur(const TraceArgs a, const m
             const unsigned slot = atomicAdd(qcount, 1u);
             queue[slot] = a.first + j;
         }
+        __syncthreads();   // the inputs of this round are read before the next round writes them
     }
 }
 

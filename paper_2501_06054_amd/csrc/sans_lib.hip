@@ -1684,15 +1684,17 @@ int run_surrogate(sans_model_s* m, const TraceArgs& a, const SurConst& sc, doubl
     }
     const LdsLayout lay = layout(m, false);
     const size_t shmem = lds_bytes(lay);
+    if ((rc = set_lds_limit((const void*)sur_kernel(m->p.kind), sur::kSurLdsBytes))) return rc;
     for (uint64_t c0 = 0; c0 < a.n; c0 += chunk) {
         TraceArgs ac = a;
         ac.first = a.first + c0;
         ac.n = std::min<uint64_t>(chunk, a.n - c0);
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, s, m->d_qcount, 1);
-        const uint64_t blocks = (ac.n + kBlock - 1) / kBlock;
-        const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)m->num_cu * 8));
-        hipLaunchKernelGGL(sur_kernel(m->p.kind), dim3(grid), dim3(kBlock), 0, s, ac, m->d_sur_pack, m->d_sur_w,
-                           sc, det, m->d_queue, m->d_qcount);
+        // one workgroup per CU: its LDS holds a hidden layer's 128 KiB of fragments
+        const uint64_t blocks = (ac.n + sur::kSurBlock - 1) / sur::kSurBlock;
+        const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(blocks, (uint64_t)m->num_cu));
+        hipLaunchKernelGGL(sur_kernel(m->p.kind), dim3(grid), dim3(sur::kSurBlock), sur::kSurLdsBytes, s, ac,
+                           m->d_sur_pack, m->d_sur_w, sc, det, m->d_queue, m->d_qcount);
         hipLaunchKernelGGL(sur_queue_kernel(m->p.kind), dim3((unsigned)m->num_cu * 2), dim3(kBlock), shmem, s,
                            ac, lay, m->d_queue, m->d_qcount, det);
         HIP_TRY(hipGetLastError());

@@ -2,7 +2,9 @@
 //
 // Every wave evaluates the network for its own 64 neutrons, 32 at a time
 // (two column groups of 16 sharing each weight fragment), with the
-// activations held in registers from layer to layer:
+// activations held in registers from layer to layer (forward32: fragments
+// read by every wave from L2; forward32_lds, the tracer's form: staged in LDS
+// once per workgroup and layer):
 //   D[16 features][16 samples] += A[16 features][32 inputs] * B[32 inputs][16 samples]
 // (v_mfma_f32_16x16x32_bf16).  Lane (g = lane/16, r = lane%16) holds, for
 // output tile t, the features 16t + 4g + i (i = 0..3) of sample r.  The
@@ -219,6 +221,134 @@ __device__ __forceinline__ void forward32(__amdgpu_buffer_rsrc_t rp, __amdgpu_bu
                 for (int i = 0; i < 4; ++i) y[gi] = __builtin_fmaf(mlp::silu(acc[gi][i] + b[i]), w4[i], y[gi]);
             asm volatile("" : "+v"(y[0]), "+v"(y[1]));
         }
+    }
+    float b4[4];
+    load4(rw, 0, mlp::kOffB4, b4);
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi) {
+        y[gi] += __shfl_xor(y[gi], 16);
+        y[gi] += __shfl_xor(y[gi], 32);
+        y[gi] += b4[0];
+    }
+}
+
+// ------------------------------------------------------------------ LDS-staged form
+// The same network with the weights staged in LDS, one layer at a time, for a
+// whole workgroup: kSurBlock lanes (kSurWaves waves) trace their neutrons,
+// then every wave evaluates its 64 samples in two passes of 32 (column groups
+// c0, c0 + 1 as above) with each layer's fragments read from LDS.  One copy of
+// a layer from L2 serves kSurWaves x 32 samples, instead of 32 when every
+// wave reads the fragments itself.
+constexpr int kSurBlock = 512;
+constexpr int kSurWaves = kSurBlock / 64;
+// LDS: the largest layer's fragments (a hidden layer, 128 KiB), then the
+// waves' inputs [kSurWaves][64][kIn] floats
+constexpr size_t kSurLdsWeights = 16 * (size_t)kPackL;
+constexpr size_t kSurLdsBytes = kSurLdsWeights + sizeof(float) * kSurBlock * kIn;
+
+// Copies n 16-byte fragments from global memory to LDS with the whole
+// workgroup, between two barriers (the previous layer's fragments are no
+// longer read; the new ones are all in place).
+__device__ __forceinline__ void stage_layer(bf16x8* __restrict__ dst, const bf16x8* __restrict__ src, int n)
+{
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kSurBlock) dst[i] = src[i];
+    __syncthreads();
+}
+
+// forward32 with the fragments in LDS (wl, staged here layer by layer from
+// pk); every wave of the workgroup must call it together.
+__device__ __forceinline__ void forward32_lds(const bf16x8* __restrict__ pk, bf16x8* __restrict__ wl,
+                                              __amdgpu_buffer_rsrc_t rw, const float* xs, int c0, float y[2])
+{
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, r = lane & 15;
+    // layer 0's fragments; the barriers also publish the inputs xs
+    stage_layer(wl, pk, (int)kPack0);
+    bf16x8 b0[2];
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = perm_k(g, j);
+            const float xv = k < 2 * kIn ? xs[(16 * (c0 + gi) + r) * kIn + (k % kIn)] : 0.0f;
+            b0[gi][j] = k < kIn ? mlp::bf16_hi(xv) : k < 2 * kIn ? mlp::bf16_lo(xv) : (__bf16)0.0f;
+        }
+    bf16x8 act[2][kSteps];
+#pragma unroll
+    for (int t = 0; t < kTiles; t += 2) {
+        const bf16x8 fa = wl[t * 64 + lane], fb = wl[(t + 1) * 64 + lane];
+        float ba[4], bb[4];
+        load4(rw, g, mlp::offB(0) + 16 * t, ba);
+        load4(rw, g, mlp::offB(0) + 16 * (t + 1), bb);
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi) {
+            const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+            const f32x4 a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, b0[gi], z, 0, 0, 0);
+            const f32x4 a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb, b0[gi], z, 0, 0, 0);
+            act_to_bf16(a0, ba, act[gi][t / 2], 0);
+            act_to_bf16(a1, bb, act[gi][t / 2], 1);
+            settle(act[gi][t / 2]);
+        }
+    }
+    // hidden layers 1..2
+#pragma unroll 1
+    for (int l = 1; l < 3; ++l) {
+        stage_layer(wl, pk + kPack0 + (int64_t)(l - 1) * kPackL, (int)kPackL);
+        bf16x8 nxt[2][kSteps];
+#pragma unroll
+        for (int t = 0; t < kTiles; t += 2) {
+            asm volatile("" ::: "memory");
+            f32x4 acc[2][2];
+#pragma unroll
+            for (int gi = 0; gi < 2; ++gi) acc[gi][0] = acc[gi][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s = 0; s < kSteps; ++s) {
+                const bf16x8 fa = wl[(t * kSteps + s) * 64 + lane];
+                const bf16x8 fb = wl[((t + 1) * kSteps + s) * 64 + lane];
+#pragma unroll
+                for (int gi = 0; gi < 2; ++gi) {
+                    acc[gi][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, act[gi][s], acc[gi][0], 0, 0, 0);
+                    acc[gi][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb, act[gi][s], acc[gi][1], 0, 0, 0);
+                }
+            }
+            float ba[4], bb[4];
+            load4(rw, g, mlp::offB(l) + 16 * t, ba);
+            load4(rw, g, mlp::offB(l) + 16 * (t + 1), bb);
+#pragma unroll
+            for (int gi = 0; gi < 2; ++gi) {
+                act_to_bf16(acc[gi][0], ba, nxt[gi][t / 2], 0);
+                act_to_bf16(acc[gi][1], bb, nxt[gi][t / 2], 1);
+                settle(nxt[gi][t / 2]);
+            }
+        }
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+            for (int s = 0; s < kSteps; ++s) act[gi][s] = nxt[gi][s];
+    }
+    // hidden layer 3 and the output layer
+    stage_layer(wl, pk + kPack0 + 2 * kPackL, (int)kPackL);
+    y[0] = y[1] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < kTiles; ++t) {
+        asm volatile("" ::: "memory");
+        f32x4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+        for (int s = 0; s < kSteps; ++s) {
+            const bf16x8 f = wl[(t * kSteps + s) * 64 + lane];
+#pragma unroll
+            for (int gi = 0; gi < 2; ++gi)
+                acc[gi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f, act[gi][s], acc[gi], 0, 0, 0);
+        }
+        float b[4], w4[4];
+        load4(rw, g, mlp::offB(3) + 16 * t, b);
+        load4(rw, g, mlp::kOffW4 + 16 * t, w4);
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) y[gi] = __builtin_fmaf(mlp::silu(acc[gi][i] + b[i]), w4[i], y[gi]);
+        asm volatile("" : "+v"(y[0]), "+v"(y[1]));
     }
     float b4[4];
     load4(rw, 0, mlp::kOffB4, b4);
