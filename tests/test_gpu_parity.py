@@ -661,7 +661,8 @@ def test_full_size_independent_widths(S, name):
                                   "teubner_strey", "sticky_coreshell", "mass_surface_fractal", "lamellar_caille",
                                   "pearl_necklace", "polymer_excl_volume", "binary_hard_sphere",
                                   "raspberry", "oriented_belt_bicelle", "adsorbed_layer",
-                                  "attenuated_coreshell", "flexible_cylinder_elliptical"])
+                                  "attenuated_coreshell", "flexible_cylinder_elliptical", "charged_spheres",
+                                  "flexible_cylinder"])
 def test_full_size_sampled(S, name):
     """1e9- and 1e8-neutron workloads: the full run equals the sum of its chunks, and
     windows spread over the whole index range match the oracle neutron by
