@@ -476,12 +476,13 @@ typedef struct {
 
 typedef struct sans_model_s* sans_model_t;
 
-/* Validates p, builds the inverse-CDF tables (standard normal, Schulz or
- * positive-Gaussian quantiles, FP64, staged in LDS by the kernels; M knots
- * equally spaced in t = -ln(2 min(u, 1 - u)) with step 32 ln 2 / (M/2 - 1):
- * knot j < M/2 at u = e^(-j dt)/2, knot M/2 + j at u = 1 - e^(-j dt)/2, so
- * that both tails, which carry the high size moments the weight divides by,
- * are tabulated to the farthest probability a 32-bit uniform reaches)
+/* Validates p, builds the inverse-CDF tables (FP64, staged in LDS by the
+ * kernels: the sizes' Schulz or positive-Gaussian quantiles at M knots
+ * equally spaced in t = -ln(2 min(u, 1 - u)) with step 32 ln 2 / (M/2 - 1),
+ * knot j < M/2 at u = e^(-j dt)/2 and knot M/2 + j at u = 1 - e^(-j dt)/2,
+ * so that both tails, which carry the high size moments the weight divides
+ * by, are tabulated to the farthest probability a 32-bit uniform reaches;
+ * the orientation's standard normal quantiles at u = (k + 1/2)/M)
  * and the model constants.  *out receives an opaque handle owning its device
  * buffers.  Errors: SANS_E_INVALID_ARG (null pointers, wrong abi_version, a
  * size <= 0, a cap radius below the cylinder radius, negative widths or

@@ -162,6 +162,8 @@ def lib():
         L.orc_table_schulz.argtypes = [i32, d, P(d)]
         L.orc_table_lookup.argtypes = [P(d), i32, d]
         L.orc_table_lookup.restype = d
+        L.orc_table_lookup_u.argtypes = [P(d), i32, d]
+        L.orc_table_lookup_u.restype = d
         L.orc_mean_volume.argtypes = [P(OrcParams)]
         L.orc_mean_volume.restype = d
         L.orc_gauss_legendre.argtypes = [i32, P(d), P(d)]
@@ -318,6 +320,12 @@ def table_schulz(M: int, p: float) -> np.ndarray:
     out = np.zeros(M)
     lib().orc_table_schulz(M, p, _ptr(out, C.c_double))
     return out
+
+
+def table_lookup_u(knots: np.ndarray, u: float) -> float:
+    """Lookup in the orientation's normal table (knots at (k + 1/2)/M)."""
+    k = np.ascontiguousarray(knots, dtype=np.float64)
+    return lib().orc_table_lookup_u(_ptr(k, C.c_double), len(k), u)
 
 
 def table_lookup(knots: np.ndarray, u: float) -> float:

@@ -303,7 +303,7 @@ double orc_truncnorm_quantile(double u, double p)
     return 1.0 + p * orc_normal_quantile(c0 + u * (1.0 - c0));
 }
 
-/* Inverse-CDF tables.  The knots are equally spaced in
+/* Inverse-CDF tables of the sizes.  The knots are equally spaced in
  * t = -ln(2 min(u, 1 - u)), which places them densely in both tails: with
  * H = M/2 and dt = 32 ln 2 / (H - 1) (t = 32 ln 2 is the farthest tail a
  * 32-bit uniform reaches, u = 2^-33), knot j < H is F^-1(e^(-j dt)/2) (the
@@ -312,14 +312,12 @@ double orc_truncnorm_quantile(double u, double p)
  * upper tail's probability, so the far tail keeps its precision. */
 static double table_dt(int32_t M) { return 32.0 * log(2.0) / (M / 2 - 1); }
 
+/* The orientation's normal table keeps knots at u = (k + 1/2)/M, linear in
+ * u: its far tails carry no moment the weight divides by, and this lookup
+ * needs no logarithm. */
 void orc_table_normal(int32_t M, double* knots)
 {
-    const int H = M / 2;
-    for (int j = 0; j < H; ++j) {
-        double q = orc_normal_quantile(0.5 * exp(-j * table_dt(M)));
-        knots[j] = q;
-        knots[H + j] = -q;
-    }
+    for (int k = 0; k < M; ++k) knots[k] = orc_normal_quantile((k + 0.5) / M);
 }
 
 void orc_table_schulz(int32_t M, double p, double* knots)
@@ -350,6 +348,20 @@ static void size_table(const orc_params* p, double* knots)
 {
     if (p->poly_kind == 1) orc_table_truncnorm(p->table_size, p->poly, knots);
     else orc_table_schulz(p->table_size, p->poly, knots);
+}
+
+/* Lookup in the normal table: s = u M - 1/2, k = clamp(floor(s), 0, M - 2),
+ * linear interpolation between knots k and k + 1 (linear extrapolation in
+ * the two end half-cells). */
+double orc_table_lookup_u(const double* knots, int32_t M, double u)
+{
+    double s = u * M - 0.5;
+    double fk = floor(s);
+    if (fk < 0.0) fk = 0.0;
+    if (fk > M - 2) fk = M - 2;
+    int k = (int)fk;
+    double f = s - fk;
+    return knots[k] + f * (knots[k + 1] - knots[k]);
 }
 
 /* Table lookup: t = -ln(2 min(u, 1 - u)), s = t/dt, j = min(floor(s),
@@ -2106,7 +2118,7 @@ static orc_event trace_one(const orc_ctx* cx, uint64_t i, uint64_t seed, uint32_
         if (p->orient_kind == 1) {
             for (int a = 0; a < 3; ++a)
                 ang[a] = p->orient_mean[a]
-                       + p->orient_sigma[a] * orc_table_lookup(cx->tab_norm, p->table_size, u[9 + a]);
+                       + p->orient_sigma[a] * orc_table_lookup_u(cx->tab_norm, p->table_size, u[9 + a]);
         } else if (p->orient_kind == 2) {
             ang[0] = acos(2.0 * u[9] - 1.0);
             ang[1] = 2.0 * ORC_PI * u[10];

@@ -554,7 +554,20 @@ __device__ __forceinline__ float struct_factor(const TraceArgs& a, float q)
     return rcpf(inv);
 }
 
-// Inverse-CDF lookup in an FP64 table whose knots are equally spaced in
+// Lookup in the orientation's FP64 normal table (knots at (k + 1/2)/M),
+// linear in u with linear extrapolation in the end half-cells.
+__device__ __forceinline__ double table_lerp_u(const double* tab, int M, double u)
+{
+    const double s = __builtin_fma(u, (double)M, -0.5);
+    double fk = floor(s);
+    fk = fmin(fmax(fk, 0.0), (double)(M - 2));
+    const int k = (int)fk;
+    const double f = s - fk;
+    const double y0 = tab[k], y1 = tab[k + 1];
+    return __builtin_fma(f, y1 - y0, y0);
+}
+
+// Inverse-CDF lookup in an FP64 size table whose knots are equally spaced in
 // t = -ln(2 min(u, 1 - u)) with step 32 ln 2 / (M/2 - 1): the lower half
 // (knots 0 .. M/2 - 1, from the median down) for u < 1/2, else the upper half
 // (from the median up), linear in t.  t and the interpolation fraction are
@@ -2132,12 +2145,12 @@ __device__ __forceinline__ Event trace_neutron(const TraceArgs& a, uint64_t i,
             if constexpr (kAniso<KIND>) {
                 if (a.orient_kind == 1) {
                     rotate_by(a.ang_sin[0], a.ang_cos[0],
-                              a.ang_sigma[0] * table_lerp(tab_norm, a.M, u64(r2.y)), g.st, g.ct);
+                              a.ang_sigma[0] * table_lerp_u(tab_norm, a.M, u64(r2.y)), g.st, g.ct);
                     rotate_by(a.ang_sin[1], a.ang_cos[1],
-                              a.ang_sigma[1] * table_lerp(tab_norm, a.M, u64(r2.z)), g.sp, g.cp);
+                              a.ang_sigma[1] * table_lerp_u(tab_norm, a.M, u64(r2.z)), g.sp, g.cp);
                     if constexpr (!kOneAxis<KIND>)
                         rotate_by(a.ang_sin[2], a.ang_cos[2],
-                                  a.ang_sigma[2] * table_lerp(tab_norm, a.M, u64(r2.w)), g.ss, g.cs);
+                                  a.ang_sigma[2] * table_lerp_u(tab_norm, a.M, u64(r2.w)), g.ss, g.cs);
                 } else if (a.orient_kind == 2) {
                     // cos(theta) uniform in [-1, 1]; phi, Psi uniform in [0, 2 pi)
                     g.ct = __builtin_fma(2.0, u64(r2.y), -1.0);

@@ -224,11 +224,7 @@ double table_tail(int j, int M) { return 0.5 * std::exp(-j * (32.0 * std::log(2.
 
 void normal_table(int M, double* out)
 {
-    const int H = M / 2;
-    for (int j = 0; j < H; ++j) {
-        out[j] = normal_quantile(table_tail(j, M));
-        out[H + j] = -out[j];
-    }
+    for (int k = 0; k < M; ++k) out[k] = normal_quantile((k + 0.5) / M);
 }
 
 // Upper half: 1 - u = v, so c0 + u (1 - c0) = 1 - v (1 - c0) and, the normal

@@ -15,13 +15,14 @@ void py_series(double phi, int nterms, double* c, double* abg);
 bool sticky_constants(double eta, double tau, int nterms, double* ca, double* cb, double* hbc);
 double schulz_moment(double p, int k);
 double positive_normal_quantile(double u, double p);
-// Inverse-CDF tables of M knots (M even), equally spaced in
+// Inverse-CDF tables of the sizes, M knots (M even), equally spaced in
 // t = -ln(2 min(u, 1 - u)) with step 32 ln 2 / (M/2 - 1): knot j < M/2 at
 // u = e^(-j dt)/2, knot M/2 + j at u = 1 - e^(-j dt)/2 (the upper tail from
 // its own probability).  table_tail(j, M) = e^(-j dt)/2.
 double table_tail(int j, int M);
-void normal_table(int M, double* out);
 void positive_normal_table(int M, double p, double* out);
+// The orientation's standard normal table: knots at u = (k + 1/2)/M.
+void normal_table(int M, double* out);
 double positive_normal_moment(double p, int k);
 double size_moment(int poly_kind, double p, int k);
 // Number-averaged particle volume; extra: the micelle's N and volumes.

@@ -85,9 +85,9 @@ def test_table_knots_vs_library(orc):
     assert dt == pytest.approx(32 * math.log(2) / (H - 1), rel=1e-15)
     js = np.array([0, 1, 7, 60, 170, H - 1])
     v = 0.5 * np.exp(-js * dt)
+    # the orientation's normal table: knots at (k + 1/2)/M
     tn = orc.table_normal(M)
-    np.testing.assert_allclose(tn[js], sp.ndtri(v), rtol=1e-11, atol=1e-13)
-    np.testing.assert_allclose(tn[H + js], -sp.ndtri(v), rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(tn, sp.ndtri((np.arange(M) + 0.5) / M), rtol=1e-11, atol=1e-13)
     for p in (0.1, 0.3, 0.7):
         a = 1.0 / p**2
         g = stats.gamma(a, scale=1.0 / a)
@@ -104,7 +104,7 @@ def test_table_lookup_interpolates_knots(orc):
     M = 64
     H = M // 2
     dt = orc.table_dt(M)
-    knots = orc.table_normal(M)
+    knots = orc.table_schulz(M, 0.3)
     for j in [0, 5, 17, H - 1]:
         v = 0.5 * math.exp(-j * dt)
         assert orc.table_lookup(knots, v) == pytest.approx(knots[j], rel=1e-13, abs=1e-14)
@@ -112,7 +112,14 @@ def test_table_lookup_interpolates_knots(orc):
     # halfway in t between two knots -> their mean; the median from either half
     v = 0.5 * math.exp(-9.5 * dt)
     assert orc.table_lookup(knots, v) == pytest.approx(0.5 * (knots[9] + knots[10]), rel=1e-12)
-    assert orc.table_lookup(knots, 0.5) == knots[H] == pytest.approx(knots[0], abs=1e-15)
+    assert orc.table_lookup(knots, 0.5) == knots[H] == pytest.approx(knots[0], rel=1e-13)
+    # the orientation's normal table: linear in u between knots at (k + 1/2)/M
+    tn = orc.table_normal(M)
+    for k in [0, 5, 31, 63]:
+        assert orc.table_lookup_u(tn, (k + 0.5) / M) == pytest.approx(tn[k], abs=1e-15)
+    assert orc.table_lookup_u(tn, 10.0 / M) == pytest.approx(0.5 * (tn[9] + tn[10]))
+    assert orc.table_lookup_u(tn, 0.0) == pytest.approx(tn[0] - 0.5 * (tn[1] - tn[0]))
+    assert orc.table_lookup_u(tn, 1.0) == pytest.approx(tn[-1] + 0.5 * (tn[-1] - tn[-2]))
 
 
 def _sampler_moment(orc, knots, k):
