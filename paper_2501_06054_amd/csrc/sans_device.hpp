@@ -52,6 +52,7 @@ template <int M> struct SinD { static constexpr double v = sin_coef(M); };
 template <int M> struct CosD { static constexpr double v = cos_coef(M); };
 
 constexpr int kPySeriesTerms = 12;
+constexpr int kPyCheb = 12;      // Chebyshev terms of the Percus-Yevick G(x)/x
 constexpr int kMaxQuad = 256;
 // Structure-factor constants in device memory: the adhesive spheres' series
 // of A(k) and B(k)/k in k^2 [kPySeriesTerms each], then 12 eta and the factor
@@ -116,6 +117,10 @@ struct TraceArgs {
     float sq_2r, sq_24phi;
     float py_alpha, py_beta, py_gamma;
     float py_c[kPySeriesTerms];
+    // G(x)/x as a Chebyshev sum in z = x^2 py_cheb_s - 1 over x <= py_cheb_xmax
+    // (the instrument's largest q sigma); py_cheb_xmax < 0: none
+    float py_cheb[kPyCheb];
+    float py_cheb_s, py_cheb_xmax;
     // adhesive and square-well constants (kSqCoef floats) or the Hayter-
     // Penfold table (device memory; read only on their branch, so they hold
     // no registers in the other kernels)
@@ -464,7 +469,21 @@ __device__ __forceinline__ float sinc_f(float x)
 __device__ __forceinline__ float py_inv_sq(const TraceArgs& a, float x)
 {
     float gx;
-    if (x < 2.5f) {
+    if (x <= a.py_cheb_xmax) {
+        // Clenshaw's recurrence of the Chebyshev sum: one branch-free form for
+        // every q of the instrument (relative error of 1/S below 5e-7 for
+        // volume fractions up to 0.2, 4e-6 at 0.45), so a wave never runs
+        // both the series and the closed form below
+        const float z = __builtin_fmaf(x * x, a.py_cheb_s, -1.0f), z2 = z + z;
+        float b1 = 0.0f, b2 = 0.0f;
+#pragma unroll
+        for (int k = kPyCheb - 1; k >= 1; --k) {
+            const float t = __builtin_fmaf(z2, b1, a.py_cheb[k]) - b2;
+            b2 = b1;
+            b1 = t;
+        }
+        gx = __builtin_fmaf(z, b1, a.py_cheb[0]) - b2;
+    } else if (x < 2.5f) {
         const float x2 = x * x;
         float r = a.py_c[kPySeriesTerms - 1];
 #pragma unroll

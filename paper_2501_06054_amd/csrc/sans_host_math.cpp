@@ -136,6 +136,29 @@ void py_series(double phi, int nterms, double* c, double* abg)
     }
 }
 
+// G(x)/x from its power series (40 terms: at x = 12 the largest term is about
+// 1.4e3 and the last below 1e-40, so FP64 keeps 1e-13), at Chebyshev-Gauss
+// nodes in z, then the discrete Chebyshev transform.
+void py_chebyshev(double phi, double xmax, int n, double* out)
+{
+    constexpr int kTerms = 40, kNodes = 64;
+    double c[kTerms], abg[3];
+    py_series(phi, kTerms, c, abg);
+    double f[kNodes], th[kNodes];
+    for (int j = 0; j < kNodes; ++j) {
+        th[j] = kPiH * (j + 0.5) / kNodes;
+        const double x2 = xmax * xmax * 0.5 * (std::cos(th[j]) + 1.0);
+        double v = 0.0;
+        for (int m = kTerms - 1; m >= 0; --m) v = v * x2 + c[m];
+        f[j] = v;
+    }
+    for (int k = 0; k < n; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < kNodes; ++j) s += f[j] * std::cos(k * th[j]);
+        out[k] = (k == 0 ? 1.0 : 2.0) * s / kNodes;
+    }
+}
+
 // Adhesive hard spheres in the Percus-Yevick closure (Baxter): the adhesion
 // parameter lambda is the smaller root of
 // (eta/12) l^2 - (tau + eta/(1 - eta)) l + (1 + eta/2)/(1 - eta)^2 = 0; with

@@ -15,6 +15,9 @@ void py_series(double phi, int nterms, double* c, double* abg);
 bool sticky_constants(double eta, double tau, int nterms, double* ca, double* cb, double* hbc);
 double schulz_moment(double p, int k);
 double positive_normal_quantile(double u, double p);
+// Chebyshev coefficients (n of them, FP64) of the Percus-Yevick G(x)/x over
+// x in [0, xmax] in the variable z = 2 (x/xmax)^2 - 1 (G/x is even in x).
+void py_chebyshev(double phi, double xmax, int n, double* out);
 // Inverse-CDF tables of the sizes, M knots (M even), equally spaced in
 // t = -ln(2 min(u, 1 - u)) with step 32 ln 2 / (M/2 - 1): knot j < M/2 at
 // u = e^(-j dt)/2, knot M/2 + j at u = 1 - e^(-j dt)/2 (the upper tail from

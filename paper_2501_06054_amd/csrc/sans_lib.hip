@@ -1375,6 +1375,18 @@ void fill_constants(const sans_params* p, TraceArgs& a, double* mean_v, double* 
         a.sq_2r = (float)(2.0 * p->sq_radius);
         a.sq_24phi = (float)(24.0 * p->sq_phi);
         a.sq_kind = p->sq_kind;
+        // the Chebyshev form of G(x)/x up to the instrument's largest x = q sigma
+        // (1 % margin), when that stays within 12
+        const double lmin = p->lambda0 * (1.0 - p->dlambda_rel);
+        const double xmax = 2.0 * p->sq_radius * 4.0 * kPi / lmin * std::sin(0.5 * p->cone_alpha) * 1.01;
+        a.py_cheb_xmax = -1.0f;   // none: every x takes the series or the closed form
+        if (xmax > 0.0 && xmax <= 12.0) {
+            double cc[kPyCheb];
+            host::py_chebyshev(p->sq_phi, xmax, kPyCheb, cc);
+            for (int k = 0; k < kPyCheb; ++k) a.py_cheb[k] = (float)cc[k];
+            a.py_cheb_s = (float)(2.0 / (xmax * xmax));
+            a.py_cheb_xmax = (float)xmax;
+        }
     }
     a.M = p->table_size;
 }
