@@ -354,23 +354,25 @@ __device__ __forceinline__ float sph_horner(float x2, float r)
 __device__ __forceinline__ float sph3j_long(float x2) { return sph_horner<14>(x2, SphC<15>::v); }
 
 // 3 j1(x)/x at an FP64 phase: the short series below 2, else the closed form
-// on the FP64 phase.  LONG: the long series up to x = kSphLong5 instead of
+// on the FP64 phase.  LONG: the long series up to x = kSphLongTo instead of
 // the short one up to 2, so that the lanes of a wave, which mostly lie below
-// 5, seldom split between the series and the closed form (both of which a
-// split wave runs).  Its absolute error there is below 2.3e-7, against 1e-8
-// for the other two forms: where an amplitude is a difference of nearly
-// equal spheres (vesicles, the shells of fractal aggregates) that error
-// would grow, so only the single sphere and the core-shell sphere take it.
-// The choice is the lane's own, so a neutron's weight does not depend on
-// which neutrons share its wave.
-constexpr float kSphLong5 = 5.0f;
+// it, seldom split between the series and the closed form (both of which a
+// split wave runs).  Its absolute error there is below 1.3e-7, against 1e-8
+// for the other two forms; the bound stays below the first zero of j1
+// (4.493), so its relative error stays below 5e-6 (F(4.3) = 0.030).  Where
+// an amplitude is a difference of nearly equal spheres (vesicles, the shells
+// of fractal aggregates) the absolute error would grow relative to it, so
+// only the single sphere and the core-shell sphere take it.  The choice is
+// the lane's own, so a neutron's weight does not depend on which neutrons
+// share its wave.
+constexpr float kSphLongTo = 4.3f;
 template <bool LONG = false>
 __device__ __forceinline__ float sph3j_d(double xd)
 {
     xd = fabs(xd);
     const float x = (float)xd;
     if constexpr (LONG)
-        if (x <= kSphLong5) return sph3j_long(x * x);
+        if (x <= kSphLongTo) return sph3j_long(x * x);
     if (x < 2.0f) return sph3j_series(x);
     float s, c;
     sincos_phase(xd, s, c);

@@ -321,6 +321,9 @@ PER_NEUTRON = {
     "attenuated_coreshell": (dict(W.workload("coreshell_py")["params"], mu_att=150.0), 30011),
     "attenuated_wide_cone_cylinder": (W.params(kind="cylinder", size=(20.0, 200.0, 0), orient_kind="isotropic",
                                                cone_alpha=1.0, sample_d=0.003, mu_att=400.0), 30011),
+    # monodisperse spheres whose q R crosses the first zero of j1 (4.49) and
+    # the long series' bound (4.3): the weight near the zero ring
+    "sphere_through_first_zero": (W.params(kind="sphere", size=(100.0, 0, 0), sld=(1e-6, 0, 0)), 30011),
     # Hayter-Penfold charged spheres (the Ornstein-Zernike solve at set-up,
     # S tabulated over the instrument's q range)
     "charged_spheres": (W.workload("charged_spheres")["params"], 30011),
@@ -379,7 +382,7 @@ DET_CASES = ["tiny_sphere", "coreshell_py", "oriented_cylinder", "oriented_ellip
              "adsorbed_layer", "pringle_iso", "attenuated_coreshell", "poly_sep_cylinder",
              "poly_sep_parallelepiped", "poly_sep_ellipsoid_gauss", "flexible_cylinder_elliptical",
              "flexcyl_flexible_flat", "charged_spheres", "hayter_strong_cylinder", "flexible_cylinder",
-             "guided_coreshell"]
+             "guided_coreshell", "sphere_through_first_zero"]
 
 
 @pytest.mark.parametrize("name", DET_CASES)
