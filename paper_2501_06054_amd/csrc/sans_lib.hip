@@ -2323,6 +2323,13 @@ struct BatchCache {
     hipGraphExec_t exec = nullptr;
     std::string graph_key;
     std::map<std::string, BatchSchedule> tuned;  // key -> schedule (this process)
+    // the Schulz tables in d_tables were built from these jobs (with M knots,
+    // in this allocation): a call with the same jobs reuses them, as a model
+    // reuses the tables it built when created
+    std::vector<SchulzJob> built_jobs;
+    double* built_tables = nullptr;
+    size_t built_cap = 0;
+    int built_M = 0;
 
     void release()
     {
@@ -2335,6 +2342,8 @@ struct BatchCache {
         if (d_tiles) (void)hipFree(d_tiles);
         if (d_jobs) (void)hipFree(d_jobs);
         if (d_tables) (void)hipFree(d_tables);
+        built_jobs.clear();
+        built_tables = nullptr;
         if (d_norm) (void)hipFree(d_norm);
         if (d_caps) (void)hipFree(d_caps);
         if (d_counter) (void)hipFree(d_counter);
@@ -2490,9 +2499,6 @@ int run_batch(BatchCache& c, int n_exp, const std::vector<TraceArgs>& exps,
         HIP_TRY(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
         const size_t ndet = (size_t)n_exp * npix;
         hipLaunchKernelGGL(k_fill, dim3((unsigned)((ndet + 255) / 256)), dim3(256), 0, c.cap_stream, dets, ndet);
-        if (!jobs.empty())
-            hipLaunchKernelGGL(k_schulz_tables, dim3((unsigned)jobs.size()), dim3(kSchulzBlock), 0,
-                               c.cap_stream, c.d_jobs, M, c.d_tables, gl16_nodes());
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, c.cap_stream, c.d_counter, 1);
         const unsigned grid = (unsigned)std::max(1, std::min(ntiles, num_cu * sc.occ));
         hipLaunchKernelGGL(batch_kernel(), dim3(grid), dim3(kHistBlock), lds, c.cap_stream, c.d_exps, c.d_tiles,
@@ -2503,6 +2509,24 @@ int run_batch(BatchCache& c, int n_exp, const std::vector<TraceArgs>& exps,
         if (ee != hipSuccess) return fail(SANS_E_HIP, std::string("graph capture: ") + hipGetErrorString(ee));
         HIP_TRY(hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0));
         c.graph_key = key.str();
+    }
+    // the Schulz tables, unless this allocation already holds them for these
+    // very jobs (then they are what the builder would write again)
+    const bool tables_ready = c.built_tables == c.d_tables && c.built_cap == c.tables_cap && c.built_M == M
+                              && c.built_jobs.size() == jobs.size()
+                              && (jobs.empty()
+                                  || std::memcmp(c.built_jobs.data(), jobs.data(), sizeof(SchulzJob) * jobs.size()) == 0);
+    if (!tables_ready) {
+        c.built_tables = nullptr;
+        if (!jobs.empty()) {
+            hipLaunchKernelGGL(k_schulz_tables, dim3((unsigned)jobs.size()), dim3(kSchulzBlock), 0, s, c.d_jobs, M,
+                               c.d_tables, gl16_nodes());
+            HIP_TRY(hipGetLastError());
+        }
+        c.built_jobs = jobs;
+        c.built_tables = c.d_tables;
+        c.built_cap = c.tables_cap;
+        c.built_M = M;
     }
     HIP_TRY(hipGraphLaunch(c.exec, s));
     return SANS_OK;
