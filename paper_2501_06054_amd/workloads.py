@@ -424,7 +424,7 @@ def poly_sep_cylinder() -> dict:
     Eq. (8); Results: the cylinder's parameter vector carries separate
     spreads of r and L), relative widths 0.15 and 0.25, R = 20 A, L = 400 A,
     axis Gaussian-spread 10 deg about x, 256x256, 1e8 neutrons."""
-    return dict(name="poly_sep_cylinder", n=10**8, seed=21, exp_id=0,
+    return dict(name="poly_sep_cylinder", n=10**8, seed=36, exp_id=0,
                 params=params(kind="cylinder", size=(20.0, 400.0, 0), sld=(1e-6, 0, 0),
                               phi=0.01, orient_kind="gaussian", poly_kind="gaussian",
                               poly_sep=(0.15, 0.25, 0.0),
@@ -435,7 +435,7 @@ def poly_sep_cylinder() -> dict:
 def poly_sep_parallelepiped() -> dict:
     """Isotropic parallelepipeds 20 x 40 x 120 A, each edge with its own
     positive-Gaussian width (0.1, 0.2, 0.3), 128x128, 1e8 neutrons."""
-    return dict(name="poly_sep_parallelepiped", n=10**8, seed=22, exp_id=0,
+    return dict(name="poly_sep_parallelepiped", n=10**8, seed=37, exp_id=0,
                 params=params(kind="parallelepiped", size=(20.0, 40.0, 120.0), sld=(1e-6, 0, 0),
                               phi=0.01, orient_kind="isotropic", poly_kind="gaussian",
                               poly_sep=(0.1, 0.2, 0.3)))
@@ -446,7 +446,7 @@ def flexible_cylinder_elliptical() -> dict:
     the paper's GPU runs fastest against MPI): contour length 1000 A, Kuhn
     length 100 A, minor radius 20 A, axis ratio 1.5, the chain and section
     integrals by 48-point rules, 256x256, 1e8 neutrons."""
-    return dict(name="flexible_cylinder_elliptical", n=10**8, seed=23, exp_id=0,
+    return dict(name="flexible_cylinder_elliptical", n=10**8, seed=38, exp_id=0,
                 params=params(kind="flexible_cylinder_elliptical", size=(20.0, 1000.0, 0), sld=(1e-6, 0, 0),
                               phi=0.01, extra=(100.0, 1.5, 0, 0), quad_n=48, nx=256, ny=256))
 
@@ -465,7 +465,7 @@ def charged_spheres() -> dict:
     """Charged spheres (Schulz radius 45 A, sigma/mean 0.1) at volume fraction
     0.12 with the Hayter-Penfold S(Q) of radius 45 A: contact potential 6 kT,
     screening kappa sigma = 1.8; 256x256, 1e8 neutrons."""
-    return dict(name="charged_spheres", n=10**8, seed=34, exp_id=0,
+    return dict(name="charged_spheres", n=10**8, seed=39, exp_id=0,
                 params=params(kind="sphere", size=(45.0, 0, 0), sld=(1e-6, 0, 6.3e-6), phi=0.12, poly=0.1,
                               sq_phi=0.12, sq_radius=45.0, sq_kind="hayter_msa", sq_extra=(6.0, 1.8),
                               nx=256, ny=256))
