@@ -147,55 +147,56 @@ __global__ __launch_bounds__(kHistBlock) void k_trace_hist(const TraceArgs a, Ld
 // Binned tally, pass 1: the events of one chunk of neutrons go to the
 // bucket of their detector tile (rows [t*rows, (t+1)*rows)).  Every wave owns
 // one private segment per tile, so no two waves ever write the same
-// counter: ranks come from ballots, and lane t of the wave keeps the running
-// count of tile t in a register (ntiles <= 64).  At the end each wave stores
-// its per-tile counts.  An event is (pixel within the tile, FP32 weight bits).
-constexpr int kEmitBlock = 256;
+// counter.  A lane takes its rank in the segment from an LDS atomic on the
+// wave's counter of its tile: one LDS operation per event whatever the number
+// of tiles among the wave's events (the LDS pipe, not the VALU, absorbs the
+// lanes that share a tile).  At the end each wave stores its per-tile counts.
+// An event is (pixel within the tile, FP32 weight bits); the order of events
+// within a segment is immaterial (the second pass sums them).
+// compiled for workgroups of up to 1024 lanes (the host picks the size)
+constexpr int kEmitBlockMax = 1024;
 constexpr int kMaxTiles = 64;
 
 template <int KIND, int MODE, bool ATT = false>
-__global__ __launch_bounds__(kEmitBlock) void k_emit(const TraceArgs a, LdsLayout lay, uint2* buckets,
+__global__ __launch_bounds__(kEmitBlockMax) void k_emit(const TraceArgs a, LdsLayout lay, uint2* buckets,
                                                      unsigned* seg_count, unsigned capw, int tile_pixels,
                                                      int ntiles)
 {
     extern __shared__ double lds_d[];
     const LdsPtrs lp = stage_all(a, lay, lds_d);
-    __syncthreads();
     const int lane = threadIdx.x & 63;
-    const unsigned nwaves = gridDim.x * (kEmitBlock / 64);
-    const unsigned wv = blockIdx.x * (kEmitBlock / 64) + (threadIdx.x >> 6);
-    unsigned count = 0;  // lane t: events of tile t so far
+    // LDS after the tables: ntiles counters per wave
+    unsigned* cnt = reinterpret_cast<unsigned*>(lds_d + lay.total) + (threadIdx.x >> 6) * ntiles;
+    if (lane < ntiles) cnt[lane] = 0u;
+    __syncthreads();
+    const unsigned wpb = blockDim.x >> 6;
+    const unsigned nwaves = gridDim.x * wpb;
+    const unsigned wv = blockIdx.x * wpb + (threadIdx.x >> 6);
+    const float inv_tile = 1.0f / (float)tile_pixels;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j - threadIdx.x < a.n; j += stride) {
-        int t = -1;
-        unsigned local = 0;
-        float w = 0.0f;
-        if (j < a.n) {
-            const Event ev = trace_neutron<KIND, MODE, ATT>(loop_args(kernel_args()), a.first + j, lp.tsize,
-                                                            lp.tnorm, lp.lq);
-            if (ev.pixel >= 0) {
-                t = ev.pixel / tile_pixels;
-                local = (unsigned)(ev.pixel - t * tile_pixels);
-                w = ev.w;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n; j += stride) {
+        const Event ev = trace_neutron<KIND, MODE, ATT>(loop_args(kernel_args()), a.first + j, lp.tsize,
+                                                        lp.tnorm, lp.lq);
+        if (ev.pixel >= 0) {
+            // tile = pixel / tile_pixels: the FP32 quotient (there are at most
+            // 64 tiles, so it is off by at most one) corrected by the remainder
+            int t = (int)((float)ev.pixel * inv_tile);
+            int local = ev.pixel - __mul24(t, tile_pixels);
+            if (local < 0) {
+                --t;
+                local += tile_pixels;
+            } else if (local >= tile_pixels) {
+                ++t;
+                local -= tile_pixels;
             }
-        }
-        // one round per distinct tile among the wave's events (wave-uniform
-        // control flow: the tile, its base and the ballots are scalars)
-        uint64_t pending = __ballot(t >= 0);
-        while (pending) {
-            const int tt = __builtin_amdgcn_readlane(t, (int)__builtin_ctzll(pending));
-            const uint64_t same = __ballot(t == tt);
-            const unsigned base = (unsigned)__builtin_amdgcn_readlane((int)count, tt);
-            if (t == tt) {
-                const unsigned rank = base + __builtin_amdgcn_mbcnt_hi((unsigned)(same >> 32),
-                                                                       __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
-                buckets[((size_t)tt * nwaves + wv) * capw + rank] = make_uint2(local, __float_as_uint(w));
-            }
-            if (lane == tt) count += (unsigned)__builtin_popcountll(same);
-            pending &= ~same;
+            const unsigned rank = __hip_atomic_fetch_add(cnt + t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            buckets[((size_t)t * nwaves + wv) * capw + rank] = make_uint2((unsigned)local, __float_as_uint(ev.w));
         }
     }
-    if (lane < ntiles) seg_count[(size_t)lane * nwaves + wv] = count;
+    // the counts of this wave's atomics, read back by its own lanes
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (lane < ntiles) seg_count[(size_t)lane * nwaves + wv] = __hip_atomic_load(cnt + lane, __ATOMIC_RELAXED,
+                                                                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
 template <int KIND, int MODE, bool ATT>

@@ -1582,6 +1582,19 @@ constexpr size_t kTileBytes = 128 * 1024;
 #endif
 constexpr int kBinChunkShift = SANS_BIN_CHUNK_SHIFT;
 
+// The emit kernel's launch: 512-lane workgroups, four times as many as fit
+// on the chip at once (the grid-stride loop then balances the neutrons whose
+// geometry takes the FP64 path; measured on the core-shell and oriented
+// cylinder workloads against 256 and 1024 lanes and 1 to 8 times resident)
+constexpr int kEmitBlock = 512;
+constexpr int kEmitGridPerResident = 4;
+
+// LDS of the emit kernel after its tables: one counter per tile per wave
+size_t emit_count_bytes(int ntiles)
+{
+    return sizeof(unsigned) * (size_t)(kEmitBlock / 64) * (size_t)ntiles;
+}
+
 bool hist_fits(const sans_model_s* m)
 {
     return lds_bytes(layout(m, true)) <= kLdsMax;
@@ -1605,7 +1618,7 @@ int choose_tally(const sans_model_s* m, bool extras)
         const size_t row_bytes = sizeof(double) * (size_t)m->p.nx;
         const size_t rows = kTileBytes / row_bytes;
         const size_t ntiles = rows ? ((size_t)m->p.ny + rows - 1) / rows : 0;
-        const size_t emit_lds = lds_bytes(layout(m, false)) + 2 * sizeof(unsigned) * kMaxTiles;
+        const size_t emit_lds = lds_bytes(layout(m, false)) + emit_count_bytes((int)ntiles);
         if (rows == 0 || ntiles > (size_t)kMaxTiles || emit_lds > kLdsMax) t = SANS_TALLY_GLOBAL;
     }
     return t;
@@ -1957,31 +1970,37 @@ int trace_scattered(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, u
         const int tile_pixels = rows * m->p.nx;
         const int slices = std::max(1, m->num_cu / ntiles);
         // one chunk writes at most 2^(shift + 3) / ntiles bytes of events (8 B
-        // each): about the 256 MB last-level cache; fewer, larger chunks save
-        // launches (2^27 ran 5 % faster than 2^25; beyond it, no gain)
+        // each): about the 256 MB last-level cache (2^26 to 2^29 ran within
+        // 3 % of each other)
         const uint64_t chunk =
             std::min<uint64_t>(n, std::max<uint64_t>(1u << 20, (1ull << kBinChunkShift) / ntiles));
-        // the emit grid and each wave's segment capacity (its neutrons per chunk)
-        const uint64_t eblocks = std::max<uint64_t>(
-            1, std::min<uint64_t>((chunk + kEmitBlock - 1) / kEmitBlock, (uint64_t)m->num_cu * 8));
-        const unsigned nwaves = (unsigned)eblocks * (kEmitBlock / 64);
-        const uint64_t iters = (chunk + eblocks * kEmitBlock - 1) / (eblocks * kEmitBlock);
-        const unsigned capw = (unsigned)(iters * 64);
+        // the emit grid (the workgroups that fit on the chip at once: the
+        // kernel strides over the chunk) and each wave's segment capacity
+        // (its neutrons per chunk)
+        const LdsLayout lay = layout(m, false);
+        const size_t shmem = lds_bytes(lay) + emit_count_bytes(ntiles);
+        EmitFn efn = pick_emit(m->p.kind, m->p.mode, needs_instrument(m->p));
         int rc;
+        if ((rc = set_lds_limit((const void*)efn, shmem))) return rc;
+        const int eblock = kEmitBlock;
+        int occ = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)efn, eblock, shmem));
+        const uint64_t eblocks = std::max<uint64_t>(
+            1, std::min<uint64_t>((chunk + eblock - 1) / eblock,
+                                  (uint64_t)m->num_cu * std::max(1, occ) * kEmitGridPerResident));
+        const unsigned nwaves = (unsigned)eblocks * (eblock / 64);
+        const uint64_t iters = (chunk + eblocks * eblock - 1) / (eblocks * eblock);
+        const unsigned capw = (unsigned)(iters * 64);
         if ((rc = ensure(m->d_partial, m->partial_cap, (size_t)ntiles * slices * tile_pixels))) return rc;
         if ((rc = ensure(m->d_buckets, m->bucket_cap, (size_t)ntiles * nwaves * capw))) return rc;
         if ((rc = ensure(m->d_bucket_count, m->bucket_count_cap, (size_t)ntiles * nwaves))) return rc;
         if ((rc = launch_fill(m->d_partial, (size_t)ntiles * slices * tile_pixels, s))) return rc;
-        const LdsLayout lay = layout(m, false);
-        const size_t shmem = lds_bytes(lay);
-        EmitFn efn = pick_emit(m->p.kind, m->p.mode, needs_instrument(m->p));
-        if ((rc = set_lds_limit((const void*)efn, shmem))) return rc;
         if ((rc = set_lds_limit((const void*)k_bin_accumulate, sizeof(double) * tile_pixels))) return rc;
         for (uint64_t c0 = 0; c0 < n; c0 += chunk) {
             TraceArgs ac = a;
             ac.first = first + c0;
             ac.n = std::min<uint64_t>(chunk, n - c0);
-            hipLaunchKernelGGL(efn, dim3((unsigned)eblocks), dim3(kEmitBlock), shmem, s, ac, lay, m->d_buckets,
+            hipLaunchKernelGGL(efn, dim3((unsigned)eblocks), dim3(eblock), shmem, s, ac, lay, m->d_buckets,
                                m->d_bucket_count, capw, tile_pixels, ntiles);
             HIP_TRY(hipGetLastError());
             hipLaunchKernelGGL(k_bin_accumulate, dim3((unsigned)(ntiles * slices)), dim3(kHistBlock),
