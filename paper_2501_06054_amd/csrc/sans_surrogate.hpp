@@ -2,9 +2,8 @@
 //
 // Every wave evaluates the network for its own 64 neutrons, 32 at a time
 // (two column groups of 16 sharing each weight fragment), with the
-// activations held in registers from layer to layer (forward32: fragments
-// read by every wave from L2; forward32_lds, the tracer's form: staged in LDS
-// once per workgroup and layer):
+// activations held in registers from layer to layer and the fragments staged
+// in LDS once per workgroup and layer (forward32_lds):
 //   D[16 features][16 samples] += A[16 features][32 inputs] * B[32 inputs][16 samples]
 // (v_mfma_f32_16x16x32_bf16).  Lane (g = lane/16, r = lane%16) holds, for
 // output tile t, the features 16t + 4g + i (i = 0..3) of sample r.  The
@@ -12,8 +11,8 @@
 // exactly the B operand the lane needs: K-step s, element j maps to input
 // 32s + (j < 4 ? 4g + j : 16 + 4g + j - 4) -- the outputs of tiles 2s and
 // 2s+1 of the lane itself.  The weights are pre-packed (k_pack_surrogate)
-// as A fragments in that order, 16 bytes per lane per (tile, K-step), read
-// from global memory (L2-resident, 390 KiB).
+// as A fragments in that order, 16 bytes per lane per (tile, K-step), 390 KiB
+// in global memory (L2-resident), one layer of which the LDS holds at a time.
 #pragma once
 
 #include "sans_device.hpp"
@@ -75,18 +74,12 @@ static __global__ void k_pack_surrogate(const __bf16* __restrict__ w, bf16x8* __
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x2 __attribute__((ext_vector_type(2)));
 
-// Buffer resources (base, size) for the packed fragments and the flat
-// parameters: loads then take one lane offset in a VGPR and the tile/step
-// offset in an SGPR, instead of a 64-bit address per fragment; reads past
-// the end return zero.
+// A buffer resource (base, size) for the flat parameters: loads then take
+// one lane offset in a VGPR and the element offset in an SGPR, instead of a
+// 64-bit address each; reads past the end return zero.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int bytes)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, 0x00020000);
-}
-
-__device__ __forceinline__ bf16x8 load_frag(__amdgpu_buffer_rsrc_t r, int lane_off, int soff)
-{
-    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, soff, 0));
 }
 
 // four consecutive BF16 parameters starting at element e0 + 4g, as floats
@@ -105,138 +98,28 @@ __device__ __forceinline__ void load4(__amdgpu_buffer_rsrc_t r, int g, int64_t e
 // independent accumulators live by running ahead.
 __device__ __forceinline__ void settle(bf16x8& v) { asm volatile("" : "+v"(v)); }
 
-// Bias + SiLU on an accumulator tile (biases b of the lane's 4 features),
-// converted to one half of the next B operand.
-__device__ __forceinline__ void act_to_bf16(const f32x4& acc, const float b[4], bf16x8& dst, int half)
+// The four biases of load4 as an MFMA accumulator: the tracer's layers start
+// their sums from the biases (one addition fewer per feature than adding
+// them to the finished sum).
+__device__ __forceinline__ f32x4 load4v(__amdgpu_buffer_rsrc_t r, int g, int64_t e0)
 {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) dst[4 * half + i] = (__bf16)mlp::silu(acc[i] + b[i]);
+    float v[4];
+    load4(r, g, e0, v);
+    return f32x4{v[0], v[1], v[2], v[3]};
 }
 
-// Network outputs for the 32 samples of column groups c0 and c0 + 1 of this
-// wave (samples 16 c0 + r and 16 (c0 + 1) + r).  Every weight fragment is
-// loaded once and applied to both groups, which halves the weight traffic
-// from L2 per sample.  xs: this wave's inputs in LDS, [64][8] floats.
-// Returns, in every lane (g, r), y[0] for sample 16 c0 + r and y[1] for
-// sample 16 (c0 + 1) + r.
-__device__ __forceinline__ void forward32(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rw, const float* xs,
-                                          int c0, float y[2])
+// SiLU of an accumulator tile that already holds the bias, converted to one
+// half of the next B operand.
+__device__ __forceinline__ void silu_to_bf16(const f32x4& acc, bf16x8& dst, int half)
 {
-    const int lane = threadIdx.x & 63;
-    const int g = lane >> 4, r = lane & 15;
-    const int loff = 16 * lane;
-    // input operands: feature perm_k(g, j) of each group's sample: hi parts of
-    // the 8 inputs, then their lo parts, then zeros
-    bf16x8 b0[2];
 #pragma unroll
-    for (int gi = 0; gi < 2; ++gi)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = perm_k(g, j);
-            const float xv = k < 2 * kIn ? xs[(16 * (c0 + gi) + r) * kIn + (k % kIn)] : 0.0f;
-            b0[gi][j] = k < kIn ? mlp::bf16_hi(xv) : k < 2 * kIn ? mlp::bf16_lo(xv) : (__bf16)0.0f;
-        }
-    bf16x8 act[2][kSteps];
-    // layer 0
-#pragma unroll
-    for (int t = 0; t < kTiles; t += 2) {
-        asm volatile("" ::: "memory");
-        const bf16x8 fa = load_frag(rp, loff, 1024 * t), fb = load_frag(rp, loff, 1024 * (t + 1));
-        float ba[4], bb[4];
-        load4(rw, g, mlp::offB(0) + 16 * t, ba);
-        load4(rw, g, mlp::offB(0) + 16 * (t + 1), bb);
-#pragma unroll
-        for (int gi = 0; gi < 2; ++gi) {
-            const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-            const f32x4 a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, b0[gi], z, 0, 0, 0);
-            const f32x4 a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb, b0[gi], z, 0, 0, 0);
-            act_to_bf16(a0, ba, act[gi][t / 2], 0);
-            act_to_bf16(a1, bb, act[gi][t / 2], 1);
-            settle(act[gi][t / 2]);
-        }
-    }
-    // hidden layers 1..2 (BF16 activations for the next product)
-#pragma unroll 1
-    for (int l = 1; l < 3; ++l) {
-        asm volatile("" ::: "memory");
-        const int base = (int)(16 * (kPack0 + (int64_t)(l - 1) * kPackL));
-        bf16x8 nxt[2][kSteps];
-#pragma unroll
-        for (int t = 0; t < kTiles; t += 2) {
-            // keeps the fragment loads of later tiles from being hoisted here
-            asm volatile("" ::: "memory");
-            f32x4 acc[2][2];
-#pragma unroll
-            for (int gi = 0; gi < 2; ++gi) acc[gi][0] = acc[gi][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int s = 0; s < kSteps; ++s) {
-                // at most half a tile pair's fragments in flight (registers)
-                if (s == kSteps / 2) asm volatile("" ::: "memory");
-                const bf16x8 fa = load_frag(rp, loff, base + 1024 * (t * kSteps + s));
-                const bf16x8 fb = load_frag(rp, loff, base + 1024 * ((t + 1) * kSteps + s));
-#pragma unroll
-                for (int gi = 0; gi < 2; ++gi) {
-                    acc[gi][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, act[gi][s], acc[gi][0], 0, 0, 0);
-                    acc[gi][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb, act[gi][s], acc[gi][1], 0, 0, 0);
-                }
-            }
-            float ba[4], bb[4];
-            load4(rw, g, mlp::offB(l) + 16 * t, ba);
-            load4(rw, g, mlp::offB(l) + 16 * (t + 1), bb);
-#pragma unroll
-            for (int gi = 0; gi < 2; ++gi) {
-                act_to_bf16(acc[gi][0], ba, nxt[gi][t / 2], 0);
-                act_to_bf16(acc[gi][1], bb, nxt[gi][t / 2], 1);
-                settle(nxt[gi][t / 2]);
-            }
-        }
-#pragma unroll
-        for (int gi = 0; gi < 2; ++gi)
-#pragma unroll
-            for (int s = 0; s < kSteps; ++s) act[gi][s] = nxt[gi][s];
-    }
-    // hidden layer 3 and the output layer: the FP32 activations of each
-    // output tile go straight into the lane's share of the output dot product
-    asm volatile("" ::: "memory");
-    y[0] = y[1] = 0.0f;
-    {
-        const int base = (int)(16 * (kPack0 + 2 * kPackL));
-#pragma unroll
-        for (int t = 0; t < kTiles; ++t) {
-            asm volatile("" ::: "memory");
-            f32x4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
-#pragma unroll
-            for (int s = 0; s < kSteps; ++s) {
-                const bf16x8 f = load_frag(rp, loff, base + 1024 * (t * kSteps + s));
-#pragma unroll
-                for (int gi = 0; gi < 2; ++gi)
-                    acc[gi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f, act[gi][s], acc[gi], 0, 0, 0);
-            }
-            float b[4], w4[4];
-            load4(rw, g, mlp::offB(3) + 16 * t, b);
-            load4(rw, g, mlp::kOffW4 + 16 * t, w4);
-#pragma unroll
-            for (int gi = 0; gi < 2; ++gi)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) y[gi] = __builtin_fmaf(mlp::silu(acc[gi][i] + b[i]), w4[i], y[gi]);
-            asm volatile("" : "+v"(y[0]), "+v"(y[1]));
-        }
-    }
-    float b4[4];
-    load4(rw, 0, mlp::kOffB4, b4);
-#pragma unroll
-    for (int gi = 0; gi < 2; ++gi) {
-        y[gi] += __shfl_xor(y[gi], 16);
-        y[gi] += __shfl_xor(y[gi], 32);
-        y[gi] += b4[0];
-    }
+    for (int i = 0; i < 4; ++i) dst[4 * half + i] = (__bf16)mlp::silu(acc[i]);
 }
 
-// ------------------------------------------------------------------ LDS-staged form
 // The same network with the weights staged in LDS, one layer at a time, for a
 // whole workgroup: kSurBlock lanes (kSurWaves waves) trace their neutrons,
 // then every wave evaluates its 64 samples in two passes of 32 (column groups
-// c0, c0 + 1 as above) with each layer's fragments read from LDS.  One copy of
+// c0, c0 + 1) with each layer's fragments read from LDS.  One copy of
 // a layer from L2 serves kSurWaves x 32 samples, instead of 32 when every
 // wave reads the fragments itself.
 constexpr int kSurBlock = 512;
@@ -256,8 +139,12 @@ __device__ __forceinline__ void stage_layer(bf16x8* __restrict__ dst, const bf16
     __syncthreads();
 }
 
-// forward32 with the fragments in LDS (wl, staged here layer by layer from
-// pk); every wave of the workgroup must call it together.
+// Network outputs for the 32 samples of column groups c0 and c0 + 1 of this
+// wave (samples 16 c0 + r and 16 (c0 + 1) + r), with the fragments in LDS
+// (wl, staged here layer by layer from pk); every wave of the workgroup must
+// call it together.  Every fragment read is applied to both groups.  xs:
+// this wave's inputs in LDS, [64][8] floats.  Returns, in every lane (g, r),
+// y[0] for sample 16 c0 + r and y[1] for sample 16 (c0 + 1) + r.
 __device__ __forceinline__ void forward32_lds(const bf16x8* __restrict__ pk, bf16x8* __restrict__ wl,
                                               __amdgpu_buffer_rsrc_t rw, const float* xs, int c0, float y[2])
 {
@@ -278,16 +165,13 @@ __device__ __forceinline__ void forward32_lds(const bf16x8* __restrict__ pk, bf1
 #pragma unroll
     for (int t = 0; t < kTiles; t += 2) {
         const bf16x8 fa = wl[t * 64 + lane], fb = wl[(t + 1) * 64 + lane];
-        float ba[4], bb[4];
-        load4(rw, g, mlp::offB(0) + 16 * t, ba);
-        load4(rw, g, mlp::offB(0) + 16 * (t + 1), bb);
+        const f32x4 ba = load4v(rw, g, mlp::offB(0) + 16 * t), bb = load4v(rw, g, mlp::offB(0) + 16 * (t + 1));
 #pragma unroll
         for (int gi = 0; gi < 2; ++gi) {
-            const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-            const f32x4 a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, b0[gi], z, 0, 0, 0);
-            const f32x4 a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb, b0[gi], z, 0, 0, 0);
-            act_to_bf16(a0, ba, act[gi][t / 2], 0);
-            act_to_bf16(a1, bb, act[gi][t / 2], 1);
+            const f32x4 a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, b0[gi], ba, 0, 0, 0);
+            const f32x4 a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb, b0[gi], bb, 0, 0, 0);
+            silu_to_bf16(a0, act[gi][t / 2], 0);
+            silu_to_bf16(a1, act[gi][t / 2], 1);
             settle(act[gi][t / 2]);
         }
     }
@@ -299,9 +183,14 @@ __device__ __forceinline__ void forward32_lds(const bf16x8* __restrict__ pk, bf1
 #pragma unroll
         for (int t = 0; t < kTiles; t += 2) {
             asm volatile("" ::: "memory");
+            // the accumulators start from the biases
+            const f32x4 ba = load4v(rw, g, mlp::offB(l) + 16 * t), bb = load4v(rw, g, mlp::offB(l) + 16 * (t + 1));
             f32x4 acc[2][2];
 #pragma unroll
-            for (int gi = 0; gi < 2; ++gi) acc[gi][0] = acc[gi][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int gi = 0; gi < 2; ++gi) {
+                acc[gi][0] = ba;
+                acc[gi][1] = bb;
+            }
 #pragma unroll
             for (int s = 0; s < kSteps; ++s) {
                 const bf16x8 fa = wl[(t * kSteps + s) * 64 + lane];
@@ -312,13 +201,10 @@ __device__ __forceinline__ void forward32_lds(const bf16x8* __restrict__ pk, bf1
                     acc[gi][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb, act[gi][s], acc[gi][1], 0, 0, 0);
                 }
             }
-            float ba[4], bb[4];
-            load4(rw, g, mlp::offB(l) + 16 * t, ba);
-            load4(rw, g, mlp::offB(l) + 16 * (t + 1), bb);
 #pragma unroll
             for (int gi = 0; gi < 2; ++gi) {
-                act_to_bf16(acc[gi][0], ba, nxt[gi][t / 2], 0);
-                act_to_bf16(acc[gi][1], bb, nxt[gi][t / 2], 1);
+                silu_to_bf16(acc[gi][0], nxt[gi][t / 2], 0);
+                silu_to_bf16(acc[gi][1], nxt[gi][t / 2], 1);
                 settle(nxt[gi][t / 2]);
             }
         }
@@ -333,7 +219,8 @@ __device__ __forceinline__ void forward32_lds(const bf16x8* __restrict__ pk, bf1
 #pragma unroll
     for (int t = 0; t < kTiles; ++t) {
         asm volatile("" ::: "memory");
-        f32x4 acc[2] = {{0.0f, 0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f, 0.0f}};
+        const f32x4 b = load4v(rw, g, mlp::offB(3) + 16 * t);
+        f32x4 acc[2] = {b, b};
 #pragma unroll
         for (int s = 0; s < kSteps; ++s) {
             const bf16x8 f = wl[(t * kSteps + s) * 64 + lane];
@@ -341,13 +228,12 @@ __device__ __forceinline__ void forward32_lds(const bf16x8* __restrict__ pk, bf1
             for (int gi = 0; gi < 2; ++gi)
                 acc[gi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f, act[gi][s], acc[gi], 0, 0, 0);
         }
-        float b[4], w4[4];
-        load4(rw, g, mlp::offB(3) + 16 * t, b);
+        float w4[4];
         load4(rw, g, mlp::kOffW4 + 16 * t, w4);
 #pragma unroll
         for (int gi = 0; gi < 2; ++gi)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) y[gi] = __builtin_fmaf(mlp::silu(acc[gi][i] + b[i]), w4[i], y[gi]);
+            for (int i = 0; i < 4; ++i) y[gi] = __builtin_fmaf(mlp::silu(acc[gi][i]), w4[i], y[gi]);
         asm volatile("" : "+v"(y[0]), "+v"(y[1]));
     }
     float b4[4];
