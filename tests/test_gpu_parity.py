@@ -399,6 +399,26 @@ def test_detector_parity(S, name, tally):
     m.close()
 
 
+# Detector shapes for the binned tally's row-band tiles: a tile size that is
+# not a power of two (the tile index is an FP32 quotient corrected by its
+# remainder), a band count that does not divide the rows, wide and flat
+# detectors, and the largest band count (64 tiles of 8 rows).
+BINNED_SHAPES = [(300, 301), (1000, 37), (257, 1024), (2048, 512), (64, 2000)]
+
+
+@pytest.mark.parametrize("nx,ny", BINNED_SHAPES)
+def test_binned_tally_detector_shapes(S, nx, ny):
+    p = dict(PER_NEUTRON["coreshell_py"][0], nx=nx, ny=ny)
+    n, seed = 400_009, 8
+    log(f"binned tally {nx}x{ny} n={n}")
+    m = S.Model(p, tally="binned")
+    det = m.trace(n, seed)
+    torch.cuda.synchronize()
+    ref, bar = oracle_detector_sparse(p, n, seed)
+    check_detector(det.cpu().numpy(), ref, f"binned {nx}x{ny}", **bar)
+    m.close()
+
+
 def test_uncharged_hayter_penfold_is_percus_yevick(S):
     """With no charge (U_c = 0) the mean spherical approximation of charged
     hard spheres is the Percus-Yevick closure: the detector of the Hayter-
