@@ -359,7 +359,7 @@ def sweep(m, p, seed, workload):
     rows = []
     for e in range(5, 11):
         n = 10 ** e
-        m.trace(min(n, 10 ** 7), seed, det=det)          # warm
+        m.trace(min(n, 10 ** 9), seed, det=det)          # warm: workspaces sized for this n
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
