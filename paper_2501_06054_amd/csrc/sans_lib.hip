@@ -51,16 +51,33 @@ int fail(int status, const std::string& msg)
     } while (0)
 
 
-// det[p] (+)= sum over g < G of partial[g][p]  (p < npix)
-__global__ void k_reduce_partials(double* det, const double* partial, int G, int npix, int accumulate)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npix) return;
-    double s = 0.0;
-    for (int g = 0; g < G; ++g) s += partial[(size_t)g * npix + p];
-    det[p] = accumulate ? det[p] + s : s;
-}
+// The partial sums of a detector pixel are read by kRedWaves waves of one
+// workgroup, each over every kRedWaves-th partial (a wave loads 64
+// consecutive pixels of one partial at a time: 512 B, coalesced), and added
+// in a fixed order: the result does not depend on the launch.  Workgroup b
+// takes pixels [64 b, 64 b + 64).
+constexpr int kRedWaves = 4;
+static_assert(kRedWaves == 4, "the final sums below add four wave sums");
 
+// det[p] (+)= sum over g < G of partial[g][p]  (p < npix)
+__global__ __launch_bounds__(64 * kRedWaves) void k_reduce_partials(double* det, const double* partial, int G,
+                                                                    int npix, int accumulate)
+{
+    __shared__ double part[kRedWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lane;
+    double s = 0.0;
+    if (p < npix) {
+#pragma unroll 8
+        for (int g = w; g < G; g += kRedWaves) s += partial[(size_t)g * npix + p];
+    }
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && p < npix) {
+        const double t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        det[p] = accumulate ? det[p] + t : t;
+    }
+}
 
 // Binned tally, pass 2: workgroup (t, s) sums the segments of waves
 // [s W/S, (s+1) W/S) of tile t in an LDS histogram of the tile (each of its
@@ -111,16 +128,27 @@ __global__ __launch_bounds__(kHistBlock) void k_bin_accumulate(const uint2* buck
 }
 
 // det[p] (+)= sum over the slices of tile t(p) of partial[t][s][p - t*tile]
-__global__ void k_reduce_binned(double* det, const double* partial, int tile_pixels, int slices,
-                                int npix, int accumulate)
+// (the same split over kRedWaves waves)
+__global__ __launch_bounds__(64 * kRedWaves) void k_reduce_binned(double* det, const double* partial,
+                                                                  int tile_pixels, int slices, int npix,
+                                                                  int accumulate)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npix) return;
-    const int t = p / tile_pixels, q = p - t * tile_pixels;
-    const double* src = partial + (size_t)t * slices * tile_pixels + q;
+    __shared__ double part[kRedWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int k = 0; k < slices; ++k) s += src[(size_t)k * tile_pixels];
-    det[p] = accumulate ? det[p] + s : s;
+    if (p < npix) {
+        const int t = p / tile_pixels, q = p - t * tile_pixels;
+        const double* src = partial + (size_t)t * slices * tile_pixels + q;
+#pragma unroll 8
+        for (int k = w; k < slices; k += kRedWaves) s += src[(size_t)k * tile_pixels];
+    }
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && p < npix) {
+        const double t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        det[p] = accumulate ? det[p] + t : t;
+    }
 }
 
 
@@ -1935,6 +1963,7 @@ int trace_scattered(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, u
     a.seed_hi = (uint32_t)(seed >> 32);
     a.exp_id = exp_id;
     const unsigned fill_grid = (unsigned)((npix + 255) / 256);
+    const unsigned red_grid = (unsigned)((npix + 63) / 64);   // the reductions: 64 pixels per workgroup
 
     if (m->p.mode == SANS_MODE_SURROGATE) {
         if (det_w2 || det_count) return fail(SANS_E_UNSUPPORTED, "surrogate mode: no det_w2/det_count");
@@ -1958,7 +1987,7 @@ int trace_scattered(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, u
         if ((rc = ensure(m->d_partial, m->partial_cap, (size_t)grid * npix))) return rc;
         hipLaunchKernelGGL(fn, dim3(grid), dim3(kHistBlock), shmem, s, a, lay, m->d_partial);
         HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_reduce_partials, dim3(fill_grid), dim3(256), 0, s, det, m->d_partial,
+        hipLaunchKernelGGL(k_reduce_partials, dim3(red_grid), dim3(64 * kRedWaves), 0, s, det, m->d_partial,
                            (int)grid, (int)npix, 1);
         HIP_TRY(hipGetLastError());
         return SANS_OK;
@@ -2008,7 +2037,7 @@ int trace_scattered(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, u
                                tile_pixels, slices, m->d_partial);
             HIP_TRY(hipGetLastError());
         }
-        hipLaunchKernelGGL(k_reduce_binned, dim3(fill_grid), dim3(256), 0, s, det, m->d_partial,
+        hipLaunchKernelGGL(k_reduce_binned, dim3(red_grid), dim3(64 * kRedWaves), 0, s, det, m->d_partial,
                            tile_pixels, slices, (int)npix, 1);
         HIP_TRY(hipGetLastError());
         return SANS_OK;
