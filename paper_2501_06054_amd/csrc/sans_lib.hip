@@ -81,7 +81,8 @@ __global__ __launch_bounds__(64 * kRedWaves) void k_reduce_partials(double* det,
 
 // Binned tally, pass 2: workgroup (t, s) sums the segments of waves
 // [s W/S, (s+1) W/S) of tile t in an LDS histogram of the tile (each of its
-// waves takes every 16th segment) and adds it to its own partial slot.  A
+// waves takes every 16th segment) and writes it to its own partial slot (the
+// first chunk of a call) or adds it there.  A
 // wave first reads the counts of up to 64 of its segments at once (one per
 // lane), then streams each segment with kAccUnroll loads in flight per lane
 // before their LDS atomics.
@@ -89,7 +90,7 @@ constexpr int kAccUnroll = 8;
 
 __global__ __launch_bounds__(kHistBlock) void k_bin_accumulate(const uint2* buckets, const unsigned* seg_count,
                                                                unsigned capw, unsigned nwaves, int tile_pixels,
-                                                               int slices, double* partial)
+                                                               int slices, double* partial, int overwrite)
 {
     extern __shared__ double hist[];
     const int t = blockIdx.x / slices, sl = blockIdx.x % slices;
@@ -124,7 +125,10 @@ __global__ __launch_bounds__(kHistBlock) void k_bin_accumulate(const uint2* buck
     }
     __syncthreads();
     double* out = partial + (size_t)blockIdx.x * tile_pixels;
-    for (int i = threadIdx.x; i < tile_pixels; i += blockDim.x) out[i] += hist[i];
+    if (overwrite)
+        for (int i = threadIdx.x; i < tile_pixels; i += blockDim.x) out[i] = hist[i];
+    else
+        for (int i = threadIdx.x; i < tile_pixels; i += blockDim.x) out[i] += hist[i];
 }
 
 // det[p] (+)= sum over the slices of tile t(p) of partial[t][s][p - t*tile]
@@ -2023,7 +2027,6 @@ int trace_scattered(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, u
         if ((rc = ensure(m->d_partial, m->partial_cap, (size_t)ntiles * slices * tile_pixels))) return rc;
         if ((rc = ensure(m->d_buckets, m->bucket_cap, (size_t)ntiles * nwaves * capw))) return rc;
         if ((rc = ensure(m->d_bucket_count, m->bucket_count_cap, (size_t)ntiles * nwaves))) return rc;
-        if ((rc = launch_fill(m->d_partial, (size_t)ntiles * slices * tile_pixels, s))) return rc;
         if ((rc = set_lds_limit((const void*)k_bin_accumulate, sizeof(double) * tile_pixels))) return rc;
         for (uint64_t c0 = 0; c0 < n; c0 += chunk) {
             TraceArgs ac = a;
@@ -2034,7 +2037,7 @@ int trace_scattered(sans_model_t m, uint64_t first, uint64_t n, uint64_t seed, u
             HIP_TRY(hipGetLastError());
             hipLaunchKernelGGL(k_bin_accumulate, dim3((unsigned)(ntiles * slices)), dim3(kHistBlock),
                                sizeof(double) * tile_pixels, s, m->d_buckets, m->d_bucket_count, capw, nwaves,
-                               tile_pixels, slices, m->d_partial);
+                               tile_pixels, slices, m->d_partial, c0 == 0 ? 1 : 0);
             HIP_TRY(hipGetLastError());
         }
         hipLaunchKernelGGL(k_reduce_binned, dim3(red_grid), dim3(64 * kRedWaves), 0, s, det, m->d_partial,
