@@ -275,14 +275,25 @@ def sans_model_constants(h):
     return tuple(out)
 
 
-def sans_trace_batch(params_list, n_neutrons, seeds, detectors_out, tune_cache=None,
-                     stream=None) -> None:
-    """params_list: list of dicts or sans_params; detectors_out: device float64
-    tensor [n_exp, ny, nx] (overwritten)."""
-    n = len(params_list)
-    arr = (sans_params * n)()
+def batch_params(params_list):
+    """The sans_params array of a batch (list of dicts or sans_params), built
+    once: a caller that traces the same experiments repeatedly passes it to
+    sans_trace_batch instead of the list, which is otherwise converted at
+    every call."""
+    arr = (sans_params * len(params_list))()
     for e, p in enumerate(params_list):
         arr[e] = p if isinstance(p, sans_params) else to_params(p)
+    return arr
+
+
+def sans_trace_batch(params_list, n_neutrons, seeds, detectors_out, tune_cache=None,
+                     stream=None) -> None:
+    """params_list: list of dicts or sans_params, or the array of
+    batch_params; detectors_out: device float64 tensor [n_exp, ny, nx]
+    (overwritten)."""
+    n = len(params_list)
+    arr = params_list if isinstance(params_list, C.Array) and params_list._type_ is sans_params \
+        else batch_params(params_list)
     nn = (C.c_uint64 * n)(*[int(x) for x in n_neutrons])
     sd = (C.c_uint64 * n)(*[int(x) for x in seeds])
     tc = tune_cache.encode() if tune_cache else None
