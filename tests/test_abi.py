@@ -100,6 +100,20 @@ def test_null_arguments(S):
     assert S.lib.sans_model_destroy(None) == S.SANS_OK
 
 
+def test_batch_params_array_matches_per_experiment_conversion(S):
+    """The prebuilt parameter array of a batch holds, byte for byte, what the
+    per-call conversion of the same experiments gives."""
+    from paper_2501_06054_amd import workloads as W
+    plist = [x["params"] for x in W.batch_experiments()[:17]]
+    arr = S.batch_params(plist)
+    assert isinstance(arr, C.Array) and arr._type_ is S.sans_params and len(arr) == 17
+    for e, p in enumerate(plist):
+        assert bytes(arr[e]) == bytes(S.to_params(p)), e
+    # already-converted entries pass through unchanged
+    again = S.batch_params(list(arr))
+    assert bytes(again) == bytes(arr)
+
+
 def test_unknown_poly_kind_rejected_without_gpu(S):
     from paper_2501_06054_amd import workloads as W
     sp = S.to_params(W.params(poly=0.1))
