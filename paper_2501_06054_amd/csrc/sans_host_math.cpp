@@ -141,20 +141,31 @@ void py_series(double phi, int nterms, double* c, double* abg)
 // nodes in z, then the discrete Chebyshev transform.
 void py_chebyshev(double phi, double xmax, int n, double* out)
 {
-    constexpr int kTerms = 40, kNodes = 64;
+    constexpr int kTerms = 40, kNodes = 64, kTab = 16;
+    // cos(k theta_j) at the fixed nodes theta_j = pi (j + 1/2) / kNodes, for
+    // k < kTab: computed once per process (a batch fits thousands of sets)
+    struct CosTable {
+        double c[kTab][kNodes];
+        CosTable()
+        {
+            for (int k = 0; k < kTab; ++k)
+                for (int j = 0; j < kNodes; ++j) c[k][j] = std::cos(k * (kPiH * (j + 0.5) / kNodes));
+        }
+    };
+    static const CosTable tab;
     double c[kTerms], abg[3];
     py_series(phi, kTerms, c, abg);
-    double f[kNodes], th[kNodes];
+    // the series at every node (Horner, all nodes in step)
+    double f[kNodes], x2[kNodes];
     for (int j = 0; j < kNodes; ++j) {
-        th[j] = kPiH * (j + 0.5) / kNodes;
-        const double x2 = xmax * xmax * 0.5 * (std::cos(th[j]) + 1.0);
-        double v = 0.0;
-        for (int m = kTerms - 1; m >= 0; --m) v = v * x2 + c[m];
-        f[j] = v;
+        x2[j] = xmax * xmax * 0.5 * (tab.c[1][j] + 1.0);
+        f[j] = 0.0;
     }
+    for (int m = kTerms - 1; m >= 0; --m)
+        for (int j = 0; j < kNodes; ++j) f[j] = f[j] * x2[j] + c[m];
     for (int k = 0; k < n; ++k) {
         double s = 0.0;
-        for (int j = 0; j < kNodes; ++j) s += f[j] * std::cos(k * th[j]);
+        for (int j = 0; j < kNodes; ++j) s += f[j] * (k < kTab ? tab.c[k][j] : std::cos(k * (kPiH * (j + 0.5) / kNodes)));
         out[k] = (k == 0 ? 1.0 : 2.0) * s / kNodes;
     }
 }
